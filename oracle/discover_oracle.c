@@ -1,0 +1,755 @@
+/*
+ * FP64 CPU oracle for the SISSO-style descriptor search of DISCOVER
+ * (arXiv 2602.06986).  TEST INFRASTRUCTURE ONLY: the product path never
+ * links, loads or calls this file; it exists so that the GPU library can be
+ * checked against a plain, slow, obviously correct implementation.
+ *
+ * What the paper fixes, and where:
+ *   - candidate features are generated iteratively from primary features
+ *     and an operator library, with pruning by physical constraints
+ *     (Software Description; Figure 1 caption);
+ *   - dimensional consistency removes invalid expressions early
+ *     (Physics-Informed Constraints);
+ *   - candidates are screened against the target (Figure 1 caption; SIS as
+ *     in the cited SISSO method, Summary);
+ *   - the sparse model solves the L0-constrained least squares of Eq. (1)
+ *     (Core Optimization Objective), with OMP among the search strategies
+ *     (Software Description).
+ * Everything finer (enumeration order, unit arithmetic, validity, score,
+ * duplicate rule, intercept, tolerances) is a reading of the paper where it
+ * is silent; each routine states the reading it implements.
+ *
+ * Build: gcc -O2 -fno-fast-math -ffp-contract=off -fopenmp -shared -fPIC.
+ * Parallel loops only distribute independent candidates or subsets; every
+ * reduction runs in a fixed order, so results do not depend on the number
+ * of threads.
+ *
+ * Operator codes (library order): 0 exp, 1 log, 2 sqrt, 3 sq, 4 inv,
+ * 5 add, 6 sub, 7 mul, 8 div, 9 rdiv.  A rung operator mask has bit c set
+ * when operator c is enabled at that rung.
+ *
+ * Parity unpinned by the paper: the enumeration order, the unit rules,
+ * validity thresholds, the duplicate rule and the L0 tolerances are this
+ * implementation's readings; they are pinned only by closed forms, brute
+ * force and library cross-checks in the test suite.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_MAXR 4
+#define OR_MAXB 8
+
+enum { OP_EXP = 0, OP_LOG, OP_SQRT, OP_SQ, OP_INV,
+       OP_ADD, OP_SUB, OP_MUL, OP_DIV, OP_RDIV, OP_NONE = 15 };
+
+enum { ST_VALID = 0, ST_UNIT = 1, ST_CHILD = 2, ST_NONFINITE = 3,
+       ST_CONST = 4 };
+
+/* A feature is numerically constant when its population standard deviation
+ * is at most this fraction of its root-mean-square value. */
+static const double OR_CONST_TOL = 1e-8;
+
+/* ------------------------------------------------------------------------ */
+/* Search-space description                                                  */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int p, R;
+    uint32_t ops[OR_MAXR];   /* ops[r] for r = 1..R */
+    int32_t pool[OR_MAXR];   /* partner rung for binary ops at rung r */
+    int64_t L[OR_MAXR];      /* raw size of each rung */
+    int64_t off[OR_MAXR + 1];/* off[r] = |P_{r-1}|, start of rung r */
+} space_t;
+
+static int popc(uint32_t m) { int c = 0; while (m) { c += m & 1u; m >>= 1; } return c; }
+
+static int64_t choose2(int64_t m) { return m * (m - 1) / 2; }
+
+/* Number of partner pairs at rung r: every (i, j) with j in rung r-1 and i
+ * either below j inside P_{r-1} (pool = r-1) or anywhere in P_pool. */
+static int64_t pairs_at(const space_t* s, int r) {
+    if (s->pool[r] == r - 1)
+        return choose2(s->off[r]) - choose2(s->off[r - 1]);
+    return s->L[r - 1] * s->off[s->pool[r] + 1];
+}
+
+static int space_init(space_t* s, int p, int R, const uint32_t* rung_ops,
+                      const int32_t* rung_pool) {
+    memset(s, 0, sizeof(*s));
+    if (p < 1 || R < 0 || R >= OR_MAXR) return -1;
+    s->p = p; s->R = R;
+    s->L[0] = p; s->off[0] = 0; s->off[1] = p;
+    for (int r = 1; r <= R; r++) {
+        s->ops[r] = rung_ops ? rung_ops[r] : 0x3FFu;
+        int pl = rung_pool ? rung_pool[r] : -1;
+        if (pl < 0) pl = r - 1;
+        if (pl > r - 1) return -1;
+        s->pool[r] = pl;
+        int nu = popc(s->ops[r] & 0x1Fu), nb = popc(s->ops[r] & 0x3E0u);
+        s->L[r] = (int64_t)nu * s->L[r - 1] + (int64_t)nb * pairs_at(s, r);
+        s->off[r + 1] = s->off[r] + s->L[r];
+    }
+    return 0;
+}
+
+/* Raw rung sizes L_0..L_R; returns |P_R|. */
+int64_t or_count(int p, int R, const uint32_t* rung_ops, const int32_t* rung_pool,
+                 int64_t* level_sizes) {
+    space_t s;
+    if (space_init(&s, p, R, rung_ops, rung_pool)) return -1;
+    for (int r = 0; r <= R; r++) level_sizes[r] = s.L[r];
+    return s.off[R + 1];
+}
+
+/* Enumerate the raw candidate list P_R in canonical order (the ID of a
+ * candidate is its position).  Rung r (r >= 1) holds, in this order: one
+ * block per enabled unary operator (operand runs over rung r-1 in index
+ * order), then one block per enabled binary operator (j runs over rung r-1
+ * in increasing index, i over the partner pool below j).  For each record:
+ * rung, op (OP_NONE for primaries), operand a (the unary operand, or i) and
+ * operand b (j, or -1). */
+int64_t or_enumerate(int p, int R, const uint32_t* rung_ops,
+                     const int32_t* rung_pool, int64_t cap, int8_t* rung,
+                     int8_t* op, int64_t* a, int64_t* b) {
+    space_t s;
+    if (space_init(&s, p, R, rung_ops, rung_pool)) return -1;
+    if (s.off[R + 1] > cap) return -2;
+    int64_t t = 0;
+    for (int64_t f = 0; f < p; f++) {
+        rung[t] = 0; op[t] = OP_NONE; a[t] = -1; b[t] = -1; t++;
+    }
+    for (int r = 1; r <= R; r++) {
+        for (int u = 0; u < 5; u++) {
+            if (!(s.ops[r] >> u & 1u)) continue;
+            for (int64_t x = s.off[r - 1]; x < s.off[r]; x++) {
+                rung[t] = (int8_t)r; op[t] = (int8_t)u; a[t] = x; b[t] = -1; t++;
+            }
+        }
+        for (int o = 5; o < 10; o++) {
+            if (!(s.ops[r] >> o & 1u)) continue;
+            for (int64_t j = s.off[r - 1]; j < s.off[r]; j++) {
+                int64_t ilim = (s.pool[r] == r - 1) ? j : s.off[s.pool[r] + 1];
+                for (int64_t i = 0; i < ilim; i++) {
+                    rung[t] = (int8_t)r; op[t] = (int8_t)o; a[t] = i; b[t] = j; t++;
+                }
+            }
+        }
+    }
+    return t;
+}
+
+/* Decode one ID without enumerating: walk the rung blocks, then the
+ * operator blocks, then (for pair blocks) scan j upward.  Returns 0 on
+ * success. */
+int or_decode(int p, int R, const uint32_t* rung_ops, const int32_t* rung_pool,
+              int64_t id, int8_t* rung, int8_t* op, int64_t* a, int64_t* b) {
+    space_t s;
+    if (space_init(&s, p, R, rung_ops, rung_pool)) return -1;
+    if (id < 0 || id >= s.off[R + 1]) return -2;
+    if (id < p) { *rung = 0; *op = OP_NONE; *a = -1; *b = -1; return 0; }
+    int r = 1;
+    while (id >= s.off[r + 1]) r++;
+    int64_t q = id - s.off[r];
+    *rung = (int8_t)r;
+    for (int u = 0; u < 5; u++) {
+        if (!(s.ops[r] >> u & 1u)) continue;
+        if (q < s.L[r - 1]) { *op = (int8_t)u; *a = s.off[r - 1] + q; *b = -1; return 0; }
+        q -= s.L[r - 1];
+    }
+    int64_t np = pairs_at(&s, r);
+    for (int o = 5; o < 10; o++) {
+        if (!(s.ops[r] >> o & 1u)) continue;
+        if (q < np) {
+            *op = (int8_t)o;
+            if (s.pool[r] == r - 1) {
+                int64_t j = s.off[r - 1];
+                while (q >= j) { q -= j; j++; }
+                *a = q; *b = j;
+            } else {
+                int64_t w = s.off[s.pool[r] + 1];
+                *a = q % w; *b = s.off[r - 1] + q / w;
+            }
+            return 0;
+        }
+        q -= np;
+    }
+    return -3;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Units: integer exponent vectors over B base units, stored multiplied by  */
+/* Q = 2^R so that square roots stay integral.                                */
+/* ------------------------------------------------------------------------ */
+/* Unit rule for one operator.  Returns 1 (legal) and writes the result, or
+ * 0 (dimensionally invalid). */
+static int unit_rule(int o, int B, const int32_t* ua, const int32_t* ub, int32_t* out) {
+    int k;
+    switch (o) {
+    case OP_EXP: case OP_LOG:               /* argument must be dimensionless */
+        for (k = 0; k < B; k++) if (ua[k] != 0) return 0;
+        for (k = 0; k < B; k++) out[k] = 0;
+        return 1;
+    case OP_SQRT:
+        for (k = 0; k < B; k++) if (ua[k] % 2 != 0) return 0;
+        for (k = 0; k < B; k++) out[k] = ua[k] / 2;
+        return 1;
+    case OP_SQ:  for (k = 0; k < B; k++) out[k] = 2 * ua[k]; return 1;
+    case OP_INV: for (k = 0; k < B; k++) out[k] = -ua[k]; return 1;
+    case OP_ADD: case OP_SUB:               /* operands must agree */
+        for (k = 0; k < B; k++) if (ua[k] != ub[k]) return 0;
+        for (k = 0; k < B; k++) out[k] = ua[k];
+        return 1;
+    case OP_MUL:  for (k = 0; k < B; k++) out[k] = ua[k] + ub[k]; return 1;
+    case OP_DIV:  for (k = 0; k < B; k++) out[k] = ua[k] - ub[k]; return 1;
+    case OP_RDIV: for (k = 0; k < B; k++) out[k] = ub[k] - ua[k]; return 1;
+    }
+    return 0;
+}
+
+/* Unit vector (scaled by 2^R) and legality of every record of an
+ * enumeration.  A record is legal when its operands are legal and the
+ * operator's rule accepts their units. */
+void or_units(int p, int B, const int32_t* units, int R, int64_t N,
+              const int8_t* op, const int64_t* a, const int64_t* b,
+              int32_t* uout, uint8_t* legal) {
+    const int32_t Q = 1 << R;
+    for (int64_t t = 0; t < N; t++) {
+        int32_t* u = uout + t * B;
+        if (op[t] == OP_NONE) {
+            for (int k = 0; k < B; k++) u[k] = units ? units[t * B + k] * Q : 0;
+            legal[t] = 1;
+            continue;
+        }
+        const int64_t ia = a[t], ib = b[t];
+        if (!legal[ia] || (ib >= 0 && !legal[ib])) {
+            legal[t] = 0;
+            for (int k = 0; k < B; k++) u[k] = 0;
+            continue;
+        }
+        legal[t] = (uint8_t)unit_rule(op[t], B, uout + ia * B,
+                                      ib >= 0 ? uout + ib * B : NULL, u);
+        if (!legal[t]) for (int k = 0; k < B; k++) u[k] = 0;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Values, validity and the Pearson score                                    */
+/* ------------------------------------------------------------------------ */
+static void apply_op(int o, int n, const double* x, const double* y, double* f) {
+    int s;
+    switch (o) {
+    case OP_EXP:  for (s = 0; s < n; s++) f[s] = exp(x[s]); break;
+    case OP_LOG:  for (s = 0; s < n; s++) f[s] = log(x[s]); break;
+    case OP_SQRT: for (s = 0; s < n; s++) f[s] = sqrt(x[s]); break;
+    case OP_SQ:   for (s = 0; s < n; s++) f[s] = x[s] * x[s]; break;
+    case OP_INV:  for (s = 0; s < n; s++) f[s] = 1.0 / x[s]; break;
+    case OP_ADD:  for (s = 0; s < n; s++) f[s] = x[s] + y[s]; break;
+    case OP_SUB:  for (s = 0; s < n; s++) f[s] = x[s] - y[s]; break;
+    case OP_MUL:  for (s = 0; s < n; s++) f[s] = x[s] * y[s]; break;
+    case OP_DIV:  for (s = 0; s < n; s++) f[s] = x[s] / y[s]; break;
+    case OP_RDIV: for (s = 0; s < n; s++) f[s] = y[s] / x[s]; break;
+    }
+}
+
+/* Neumaier-compensated sum. */
+static double nsum(const double* v, int n) {
+    double s = 0.0, c = 0.0;
+    for (int i = 0; i < n; i++) {
+        double t = s + v[i];
+        if (fabs(s) >= fabs(v[i])) c += (s - t) + v[i];
+        else c += (v[i] - t) + s;
+        s = t;
+    }
+    return s + c;
+}
+
+/* Numerical checks of a feature's values: all finite, finite second
+ * moment, not constant.  On success writes the mean and the centered sum of
+ * squares.  `tmp` has n entries. */
+static int feature_checks(int n, const double* f, double* tmp, double* mean, double* sxx) {
+    for (int s = 0; s < n; s++) if (!isfinite(f[s])) return ST_NONFINITE;
+    double m = nsum(f, n) / n;
+    for (int s = 0; s < n; s++) { double d = f[s] - m; tmp[s] = d * d; }
+    double ss = nsum(tmp, n);
+    if (!isfinite(ss)) return ST_NONFINITE;
+    double sd = sqrt(ss / n), rms = sqrt(ss / n + m * m);
+    if (!(sd > OR_CONST_TOL * rms)) return ST_CONST;
+    *mean = m; *sxx = ss;
+    return ST_VALID;
+}
+
+/* Pearson r of f against a centered target yc (sum of squares syy):
+ * two-pass, compensated, r = sum (f-m)(yc) / sqrt(sxx * syy). */
+static double pearson(int n, const double* f, double m, double sxx,
+                      const double* yc, double syy, double* tmp) {
+    for (int s = 0; s < n; s++) tmp[s] = (f[s] - m) * yc[s];
+    return nsum(tmp, n) / sqrt(sxx * syy);
+}
+
+/* Center every target; returns nonzero when a target is constant. */
+static int prep_targets(int n, int T, const double* Y, double* Yc, double* syy, double* tmp) {
+    for (int t = 0; t < T; t++) {
+        const double* y = Y + (int64_t)t * n;
+        double m = nsum(y, n) / n;
+        for (int s = 0; s < n; s++) Yc[(int64_t)t * n + s] = y[s] - m;
+        for (int s = 0; s < n; s++) tmp[s] = Yc[(int64_t)t * n + s] * Yc[(int64_t)t * n + s];
+        syy[t] = nsum(tmp, n);
+        double sd = sqrt(syy[t] / n), rms = sqrt(syy[t] / n + m * m);
+        if (!(sd > OR_CONST_TOL * rms)) return 1;
+    }
+    return 0;
+}
+
+/* Screen every raw candidate of P_R.  Features of rungs below R are
+ * evaluated once and kept (rung R needs them as operands); each rung-R
+ * candidate is evaluated on the fly from its two operands.
+ *   X       [p][n]; Y [T][n]
+ *   scores  [T][N]  Pearson r (signed) for valid candidates, NaN otherwise
+ *   status  [N]     ST_* code
+ * Returns the number of valid candidates, or <0 on error
+ * (-5: a constant target). */
+int64_t or_screen(int n, int p, const double* X, int T, const double* Y,
+                  int B, const int32_t* units, int R, const uint32_t* rung_ops,
+                  const int32_t* rung_pool, int64_t N, double* scores,
+                  uint8_t* status) {
+    space_t s;
+    if (space_init(&s, p, R, rung_ops, rung_pool)) return -1;
+    if (N != s.off[R + 1]) return -2;
+    int8_t* rg = malloc(N); int8_t* op = malloc(N);
+    int64_t* ia = malloc(N * 8); int64_t* ib = malloc(N * 8);
+    int32_t* uu = malloc((B ? B : 1) * N * 4); uint8_t* legal = malloc(N);
+    const int64_t M = s.off[R];                 /* |P_{R-1}| features kept */
+    double* V = malloc((M ? M : 1) * (int64_t)n * 8);
+    double* Yc = malloc((int64_t)T * n * 8); double* syy = malloc(T * 8);
+    double* tmp0 = malloc((int64_t)n * 8);
+    int64_t nvalid = 0;
+    or_enumerate(p, R, rung_ops, rung_pool, N, rg, op, ia, ib);
+    or_units(p, B, units, R, N, op, ia, ib, uu, legal);
+    if (prep_targets(n, T, Y, Yc, syy, tmp0)) { nvalid = -5; goto done; }
+    /* Rungs below R, in order (operands always precede their parents). */
+    for (int64_t t = 0; t < M; t++) {
+        double* f = V + t * n;
+        if (op[t] == OP_NONE) memcpy(f, X + t * n, (size_t)n * 8);
+        else apply_op(op[t], n, V + ia[t] * n, ib[t] >= 0 ? V + ib[t] * n : NULL, f);
+    }
+    for (int64_t t = 0; t < M; t++) {
+        if (!legal[t]) status[t] = ST_UNIT;
+        else if ((op[t] != OP_NONE) &&
+                 (status[ia[t]] != ST_VALID || (ib[t] >= 0 && status[ib[t]] != ST_VALID)))
+            status[t] = ST_CHILD;
+        else {
+            double m, sxx;
+            status[t] = (uint8_t)feature_checks(n, V + t * n, tmp0, &m, &sxx);
+        }
+    }
+    #pragma omp parallel
+    {
+        double* f = malloc((int64_t)n * 8);
+        double* tmp = malloc((int64_t)n * 8);
+        #pragma omp for schedule(dynamic, 256)
+        for (int64_t t = 0; t < N; t++) {
+            const double* fv;
+            if (t >= M) {
+                if (!legal[t]) { status[t] = ST_UNIT; goto fill; }
+                if (status[ia[t]] != ST_VALID || (ib[t] >= 0 && status[ib[t]] != ST_VALID)) {
+                    status[t] = ST_CHILD; goto fill;
+                }
+                apply_op(op[t], n, V + ia[t] * n, ib[t] >= 0 ? V + ib[t] * n : NULL, f);
+                double m, sxx;
+                status[t] = (uint8_t)feature_checks(n, f, tmp, &m, &sxx);
+                if (status[t] != ST_VALID) goto fill;
+                fv = f;
+                for (int q = 0; q < T; q++)
+                    scores[(int64_t)q * N + t] = pearson(n, fv, m, sxx, Yc + (int64_t)q * n, syy[q], tmp);
+                continue;
+            } else {
+                if (status[t] != ST_VALID) goto fill;
+                double m, sxx;
+                feature_checks(n, V + t * n, tmp, &m, &sxx);
+                for (int q = 0; q < T; q++)
+                    scores[(int64_t)q * N + t] = pearson(n, V + t * n, m, sxx, Yc + (int64_t)q * n, syy[q], tmp);
+                continue;
+            }
+        fill:
+            for (int q = 0; q < T; q++) scores[(int64_t)q * N + t] = NAN;
+        }
+        free(f); free(tmp);
+    }
+    for (int64_t t = 0; t < N; t++) nvalid += status[t] == ST_VALID;
+done:
+    free(rg); free(op); free(ia); free(ib); free(uu); free(legal);
+    free(V); free(Yc); free(syy); free(tmp0);
+    return nvalid;
+}
+
+/* Recursive evaluation of one ID from the primaries, with its status (the
+ * same rules as or_screen: unit legality, valid operands, finite values,
+ * not constant).  `f` receives n values.  Unit vectors of the operands are
+ * computed recursively as well.  Returns the ST_* code. */
+static int eval_rec(const space_t* s, int n, const double* X, int B,
+                    const int32_t* units, int64_t id, double* f, int32_t* u,
+                    double* tmp) {
+    int8_t rg, o; int64_t a, b;
+    or_decode(s->p, s->R, s->ops, s->pool, id, &rg, &o, &a, &b);
+    const int32_t Q = 1 << s->R;
+    if (o == OP_NONE) {
+        memcpy(f, X + id * n, (size_t)n * 8);
+        for (int k = 0; k < B; k++) u[k] = units ? units[id * B + k] * Q : 0;
+    } else {
+        double* fa = malloc((int64_t)n * 8); double* fb = b >= 0 ? malloc((int64_t)n * 8) : NULL;
+        int32_t ua[OR_MAXB], ub[OR_MAXB];
+        int sa = eval_rec(s, n, X, B, units, a, fa, ua, tmp);
+        int sb = b >= 0 ? eval_rec(s, n, X, B, units, b, fb, ub, tmp) : ST_VALID;
+        int leg = (sa != ST_UNIT) && (sb != ST_UNIT) && unit_rule(o, B, ua, ub, u);
+        apply_op(o, n, fa, fb, f);         /* values are returned in every case */
+        free(fa); free(fb);
+        if (!leg) { for (int k = 0; k < B; k++) u[k] = 0; return ST_UNIT; }
+        if (sa != ST_VALID || sb != ST_VALID) return ST_CHILD;
+    }
+    double m, sxx;
+    return feature_checks(n, f, tmp, &m, &sxx);
+}
+
+/* Values and status of a list of IDs, each evaluated recursively from the
+ * primaries.  values [m][n] (filled even when invalid), status [m]. */
+int or_values(int n, int p, const double* X, int B, const int32_t* units,
+              int R, const uint32_t* rung_ops, const int32_t* rung_pool,
+              int64_t m, const int64_t* ids, double* values, uint8_t* status) {
+    space_t s;
+    if (space_init(&s, p, R, rung_ops, rung_pool)) return -1;
+    for (int64_t t = 0; t < m; t++) if (ids[t] < 0 || ids[t] >= s.off[R + 1]) return -2;
+    #pragma omp parallel
+    {
+        double* tmp = malloc((int64_t)n * 8);
+        int32_t u[OR_MAXB];
+        #pragma omp for schedule(dynamic, 4)
+        for (int64_t t = 0; t < m; t++)
+            status[t] = (uint8_t)eval_rec(&s, n, X, B, units, ids[t], values + t * n, u, tmp);
+        free(tmp);
+    }
+    return 0;
+}
+
+/* Pearson r of given feature values against given targets (same formula as
+ * the screen): f [m][n], Y [T][n] -> r [T][m]; NaN for constant or
+ * non-finite features. */
+int or_pearson(int n, int64_t m, const double* F, int T, const double* Y, double* r) {
+    double* Yc = malloc((int64_t)T * n * 8); double* syy = malloc(T * 8);
+    double* tmp = malloc((int64_t)n * 8);
+    int bad = prep_targets(n, T, Y, Yc, syy, tmp);
+    if (!bad) {
+        for (int64_t t = 0; t < m; t++) {
+            double mm, sxx;
+            int st = feature_checks(n, F + t * n, tmp, &mm, &sxx);
+            for (int q = 0; q < T; q++)
+                r[(int64_t)q * m + t] = st == ST_VALID
+                    ? pearson(n, F + t * n, mm, sxx, Yc + (int64_t)q * n, syy[q], tmp) : NAN;
+        }
+    }
+    free(Yc); free(syy); free(tmp);
+    return bad ? -5 : 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Least squares (Eq. 1 restricted to one support, with an intercept)       */
+/* ------------------------------------------------------------------------ */
+/* Householder QR least squares of y on the n x m design A (column-major,
+ * overwritten).  Writes the coefficients (m), the residual sum of squares
+ * and |R_jj| (m).  Textbook Householder reflections, applied column by
+ * column; returns 0. */
+static int householder_lsq(int n, int m, double* A, double* y, double* coef,
+                           double* rss, double* rdiag) {
+    for (int j = 0; j < m; j++) {
+        double* aj = A + (int64_t)j * n;
+        double nrm = 0.0;
+        for (int i = j; i < n; i++) nrm += aj[i] * aj[i];
+        nrm = sqrt(nrm);
+        double alpha = aj[j] > 0 ? -nrm : nrm;
+        double v0 = aj[j] - alpha;
+        double vv = v0 * v0;
+        for (int i = j + 1; i < n; i++) vv += aj[i] * aj[i];
+        aj[j] = v0;                          /* v stored in place */
+        if (vv > 0.0) {
+            for (int c = j + 1; c < m; c++) {
+                double* ac = A + (int64_t)c * n;
+                double d = 0.0;
+                for (int i = j; i < n; i++) d += aj[i] * ac[i];
+                double g = 2.0 * d / vv;
+                for (int i = j; i < n; i++) ac[i] -= g * aj[i];
+            }
+            double d = 0.0;
+            for (int i = j; i < n; i++) d += aj[i] * y[i];
+            double g = 2.0 * d / vv;
+            for (int i = j; i < n; i++) y[i] -= g * aj[i];
+        }
+        rdiag[j] = alpha;
+        aj[j] = alpha;
+    }
+    /* back substitution with R (upper triangle of A, diagonal = alpha) */
+    for (int j = m - 1; j >= 0; j--) {
+        double acc = y[j];
+        for (int c = j + 1; c < m; c++) acc -= A[(int64_t)c * n + j] * coef[c];
+        coef[j] = acc / A[(int64_t)j * n + j];
+    }
+    double r = 0.0;
+    for (int i = m; i < n; i++) r += y[i] * y[i];
+    *rss = r;
+    for (int j = 0; j < m; j++) rdiag[j] = fabs(rdiag[j]);
+    return 0;
+}
+
+/* Least-squares fit of y on [1, f_1..f_d] (the columns given as pointers).
+ * coef[0] is the intercept.  Returns the RSS. */
+double or_lsq(int n, int d, const double* const* cols, const double* y, double* coef) {
+    int m = d + 1;
+    double* A = malloc((int64_t)n * m * 8); double* w = malloc((int64_t)n * 8);
+    double rd[16];
+    for (int i = 0; i < n; i++) A[i] = 1.0;
+    for (int j = 0; j < d; j++) memcpy(A + (int64_t)(j + 1) * n, cols[j], (size_t)n * 8);
+    memcpy(w, y, (size_t)n * 8);
+    double rss;
+    householder_lsq(n, m, A, w, coef, &rss, rd);
+    free(A); free(w);
+    return rss;
+}
+
+/* Squared |R_jj| of the QR of the centered, unit-norm columns (in the given
+ * order): the Cholesky pivots of their correlation matrix. */
+void or_pivots(int n, int d, const double* const* cols, double* piv) {
+    double* A = malloc((int64_t)n * d * 8); double* w = calloc(n, 8);
+    double coef[16], rd[16], rss;
+    for (int j = 0; j < d; j++) {
+        double* c = A + (int64_t)j * n;
+        memcpy(c, cols[j], (size_t)n * 8);
+        double m = nsum(c, n) / n;
+        for (int i = 0; i < n; i++) c[i] -= m;
+        double ss = 0.0;
+        for (int i = 0; i < n; i++) ss += c[i] * c[i];
+        double inv = 1.0 / sqrt(ss);
+        for (int i = 0; i < n; i++) c[i] *= inv;
+    }
+    householder_lsq(n, d, A, w, coef, &rss, rd);
+    for (int j = 0; j < d; j++) piv[j] = rd[j] * rd[j];
+    free(A); free(w);
+}
+
+/* Lexicographic successor of a D-subset of {0..S-1}; 0 when exhausted. */
+static int next_comb(int* c, int D, int S) {
+    int i = D - 1;
+    while (i >= 0 && c[i] == S - D + i) i--;
+    if (i < 0) return 0;
+    c[i]++;
+    for (int k = i + 1; k < D; k++) c[k] = c[k - 1] + 1;
+    return 1;
+}
+
+/* Direct mode: every D-subset of the S rows of F ([S][n]) in lexicographic
+ * order is fitted by Householder QR with an intercept.  rss[t] is NaN when
+ * the subset's smallest pivot (see or_pivots) is <= piv_tol.  Returns the
+ * number of subsets. */
+int64_t or_l0_direct(int n, int S, const double* F, const double* y, int D,
+                     double piv_tol, double* rss) {
+    if (D < 1 || D > 8 || S < D) return 0;
+    int64_t total = 0;
+    int c[8];
+    for (int k = 0; k < D; k++) c[k] = k;
+    do { total++; } while (next_comb(c, D, S));
+    #pragma omp parallel
+    {
+        int cc[8]; const double* cols[8]; double coef[9], piv[8];
+        #pragma omp for schedule(dynamic, 64)
+        for (int64_t t = 0; t < total; t++) {
+            /* unrank t by stepping from the start (plain, slow) */
+            int64_t rem = t; int lo = 0;
+            for (int k = 0; k < D; k++) {
+                for (int v = lo;; v++) {
+                    /* number of subsets with cc[k] = v: C(S-1-v, D-1-k) */
+                    int64_t cnt = 1; int nn = S - 1 - v, kk = D - 1 - k;
+                    for (int z = 0; z < kk; z++) cnt = cnt * (nn - z) / (z + 1);
+                    if (nn < kk) cnt = 0;
+                    if (rem < cnt) { cc[k] = v; lo = v + 1; break; }
+                    rem -= cnt;
+                }
+            }
+            for (int k = 0; k < D; k++) cols[k] = F + (int64_t)cc[k] * n;
+            or_pivots(n, D, cols, piv);
+            double mn = piv[0];
+            for (int k = 1; k < D; k++) if (piv[k] < mn) mn = piv[k];
+            rss[t] = (mn > piv_tol) ? or_lsq(n, D, cols, y, coef) : NAN;
+        }
+    }
+    return total;
+}
+
+/* Correlation matrix of the centered, unit-norm rows of F ([S][n]) and
+ * their correlations with the centered, unit-norm y:
+ *   C [S][S], c [S]; yy = sum (y - mean)^2.  Plain compensated dot
+ * products. */
+void or_corr_matrix(int n, int S, const double* F, const double* y, double* C,
+                    double* c, double* yy) {
+    double* Z = malloc((int64_t)S * n * 8); double* z = malloc((int64_t)n * 8);
+    double* tmp = malloc((int64_t)n * 8);
+    for (int a = 0; a < S; a++) {
+        const double* f = F + (int64_t)a * n; double* q = Z + (int64_t)a * n;
+        double m = nsum(f, n) / n;
+        for (int s = 0; s < n; s++) q[s] = f[s] - m;
+        for (int s = 0; s < n; s++) tmp[s] = q[s] * q[s];
+        double inv = 1.0 / sqrt(nsum(tmp, n));
+        for (int s = 0; s < n; s++) q[s] *= inv;
+    }
+    double m = nsum(y, n) / n;
+    for (int s = 0; s < n; s++) z[s] = y[s] - m;
+    for (int s = 0; s < n; s++) tmp[s] = z[s] * z[s];
+    *yy = nsum(tmp, n);
+    double inv = 1.0 / sqrt(*yy);
+    for (int s = 0; s < n; s++) z[s] *= inv;
+    #pragma omp parallel
+    {
+        double* t2 = malloc((int64_t)n * 8);
+        #pragma omp for schedule(dynamic, 4)
+        for (int a = 0; a < S; a++) {
+            const double* qa = Z + (int64_t)a * n;
+            for (int b = a; b < S; b++) {
+                const double* qb = Z + (int64_t)b * n;
+                for (int s = 0; s < n; s++) t2[s] = qa[s] * qb[s];
+                C[(int64_t)a * S + b] = C[(int64_t)b * S + a] = nsum(t2, n);
+            }
+            for (int s = 0; s < n; s++) t2[s] = qa[s] * z[s];
+            c[a] = nsum(t2, n);
+        }
+        free(t2);
+    }
+    free(Z); free(z); free(tmp);
+}
+
+/* Explained fraction q = c_S^T C_SS^{-1} c_S of one subset by Cholesky of
+ * the D x D correlation block in subset order; the pivots are the
+ * squared diagonal of the Cholesky factor.  Returns 0 when any pivot is
+ * <= piv_tol (rank-deficient), 1 otherwise. */
+static int gram_subset(int S, const double* C, const double* c, int D, const int* sub,
+                       double piv_tol, double* q) {
+    double L[8][8], z[8];
+    for (int i = 0; i < D; i++) {
+        for (int j = 0; j <= i; j++) {
+            double acc = C[(int64_t)sub[i] * S + sub[j]];
+            for (int k = 0; k < j; k++) acc -= L[i][k] * L[j][k];
+            if (i == j) {
+                if (!(acc > piv_tol)) return 0;
+                L[i][i] = sqrt(acc);
+            } else {
+                L[i][j] = acc / L[j][j];
+            }
+        }
+    }
+    double acc2 = 0.0;
+    for (int i = 0; i < D; i++) {
+        double acc = c[sub[i]];
+        for (int k = 0; k < i; k++) acc -= L[i][k] * z[k];
+        z[i] = acc / L[i][i];
+        acc2 += z[i] * z[i];
+    }
+    *q = acc2;
+    return 1;
+}
+
+/* Gram mode, used where fitting every subset by QR is too slow: the
+ * explained fraction of each D-subset from the correlation matrix
+ * (mathematically RSS = yy (1 - q)).  Pass 1 finds the m-th largest q over
+ * all non-singular subsets; pass 2 returns every subset with
+ * q >= q_(m) - delta (the band that is then refitted by QR).
+ *   band  [cap][D] positions (ascending), bq [cap]
+ * Returns the band size (which may exceed cap: then only cap are written),
+ * or -1 if fewer than one non-singular subset exists. */
+int64_t or_l0_gram_band(int S, const double* C, const double* c, int D,
+                        double piv_tol, int m, double delta, int64_t cap,
+                        int32_t* band, double* bq) {
+    if (D < 1 || D > 8 || S < D || m < 1 || m > 64) return -1;
+    double best[64]; int nb = 0;
+    #pragma omp parallel
+    {
+        double lb[64]; int ln = 0;
+        int sub[8];
+        #pragma omp for schedule(dynamic, 1)
+        for (int a = 0; a <= S - D; a++) {
+            sub[0] = a;
+            for (int k = 1; k < D; k++) sub[k] = a + k;
+            do {
+                double q;
+                if (gram_subset(S, C, c, D, sub, piv_tol, &q)) {
+                    if (ln < m || q > lb[ln - 1]) {   /* keep top-m, descending */
+                        int pos = ln < m ? ln++ : m - 1;
+                        while (pos > 0 && lb[pos - 1] < q) { lb[pos] = lb[pos - 1]; pos--; }
+                        lb[pos] = q;
+                    }
+                }
+                /* advance the tail (positions 1..D-1) keeping sub[0] = a */
+                int i = D - 1;
+                while (i >= 1 && sub[i] == S - D + i) i--;
+                if (i < 1) break;
+                sub[i]++;
+                for (int k = i + 1; k < D; k++) sub[k] = sub[k - 1] + 1;
+            } while (1);
+        }
+        #pragma omp critical
+        {
+            for (int t = 0; t < ln; t++) {
+                double q = lb[t];
+                if (nb < m || q > best[nb - 1]) {
+                    int pos = nb < m ? nb++ : m - 1;
+                    while (pos > 0 && best[pos - 1] < q) { best[pos] = best[pos - 1]; pos--; }
+                    best[pos] = q;
+                }
+            }
+        }
+    }
+    if (nb == 0) return -1;
+    const double thr = best[nb - 1] - delta;
+    int64_t count = 0;
+    #pragma omp parallel
+    {
+        int sub[8];
+        #pragma omp for schedule(dynamic, 1)
+        for (int a = 0; a <= S - D; a++) {
+            sub[0] = a;
+            for (int k = 1; k < D; k++) sub[k] = a + k;
+            do {
+                double q;
+                if (gram_subset(S, C, c, D, sub, piv_tol, &q) && q >= thr) {
+                    int64_t slot;
+                    #pragma omp atomic capture
+                    slot = count++;
+                    if (slot < cap) {
+                        for (int k = 0; k < D; k++) band[slot * D + k] = sub[k];
+                        bq[slot] = q;
+                    }
+                }
+                int i = D - 1;
+                while (i >= 1 && sub[i] == S - D + i) i--;
+                if (i < 1) break;
+                sub[i]++;
+                for (int k = i + 1; k < D; k++) sub[k] = sub[k - 1] + 1;
+            } while (1);
+        }
+    }
+    return count;
+}
+
+int or_max_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void or_set_threads(int t) {
+#ifdef _OPENMP
+    if (t > 0) omp_set_num_threads(t);
+#else
+    (void)t;
+#endif
+}
