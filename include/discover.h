@@ -1,0 +1,252 @@
+/*
+ * discover.h -- C ABI of the MI355X (gfx950) hot path of the DISCOVER /
+ * SISSO-style symbolic regression method (arXiv 2602.06986).
+ *
+ * The method (Software Description; Figure 1 caption) generates candidate
+ * expressions from primary features and an operator library, screens them
+ * against the target, and selects a sparse linear model solving the
+ * L0-constrained least squares of Eq. (1) (Core Optimization Objective).
+ * Dimensional consistency prunes candidates during generation
+ * (Physics-Informed Constraints).  Three calls cover that path:
+ *
+ *   discover_generate_screen  enumerate + unit-prune + screen + exact top-k
+ *   discover_l0_fit           exhaustive L0 over all D-subsets of a subspace
+ *   discover_omp              orthogonal matching pursuit over a subspace
+ *
+ * Conventions shared by every call
+ *   - Pointers documented as "device" are HIP device memory on the
+ *     context's device; "host" pointers are ordinary host memory.  The
+ *     caller owns every input and output buffer; the library never frees
+ *     caller memory.  The context owns only its internal workspace.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Work is
+ *     enqueued on it; every call returns after its results are complete
+ *     (calls synchronise the stream, because pool sizes are data
+ *     dependent).
+ *   - Errors: every argument is validated before any launch; on error the
+ *     call returns a negative discover_status, writes no output, and
+ *     discover_last_error() describes the failure.  No C++ exception or
+ *     abort crosses the ABI.
+ *   - A context is not thread-safe; separate contexts are independent.
+ *
+ * Candidate IDs.  Rung 0 holds the p primary features (ID = column).  Rung
+ * r >= 1 holds, in this order: one block per enabled unary operator
+ * (exp, log, sqrt, sq, inv) applied to every rung r-1 feature in index
+ * order, then one block per enabled binary operator (add, sub, mul, div,
+ * rdiv) over every pair (i, j) with j in rung r-1 (increasing) and i in
+ * the partner pool (increasing): i < j inside P_{r-1} by default, or all of
+ * P_pool for an operator-limited rung.  add = f_i + f_j, sub = f_i - f_j,
+ * mul = f_i f_j, div = f_i / f_j, rdiv = f_j / f_i.  The ID of a candidate
+ * is its position in this list; IDs never depend on data or pruning.
+ */
+#ifndef DISCOVER_H
+#define DISCOVER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DISCOVER_OK = 0,
+    DISCOVER_E_ARG = -1,          /* invalid argument (nothing launched) */
+    DISCOVER_E_NOMEM = -2,        /* device workspace allocation failed */
+    DISCOVER_E_HIP = -3,          /* a HIP runtime call failed */
+    DISCOVER_E_UNSUPPORTED = -4,  /* valid but not implemented combination */
+    DISCOVER_E_NUMERIC = -5,      /* e.g. a constant target column */
+    DISCOVER_E_CAPACITY = -6      /* an internal pool could not be grown */
+} discover_status;
+
+/* Operator bits (library order). */
+#define DISCOVER_OP_EXP  (1u << 0)
+#define DISCOVER_OP_LOG  (1u << 1)
+#define DISCOVER_OP_SQRT (1u << 2)
+#define DISCOVER_OP_SQ   (1u << 3)
+#define DISCOVER_OP_INV  (1u << 4)
+#define DISCOVER_OP_ADD  (1u << 5)
+#define DISCOVER_OP_SUB  (1u << 6)
+#define DISCOVER_OP_MUL  (1u << 7)
+#define DISCOVER_OP_DIV  (1u << 8)
+#define DISCOVER_OP_RDIV (1u << 9)
+#define DISCOVER_OPS_ALL 0x3FFu
+
+#define DISCOVER_SCORE_PER_TARGET 0   /* one top-k list per target column */
+#define DISCOVER_SCORE_MAX        1   /* one list scored by max_t |r_t| */
+
+#define DISCOVER_FP64        0        /* FP64 screening */
+#define DISCOVER_BF16_GUARD  1        /* BF16 MFMA screening + FP64 rescore of a guard band */
+#define DISCOVER_FP16_GUARD  2        /* FP16 MFMA screening + FP64 rescore of a guard band */
+
+#define DISCOVER_MAX_RUNG    3
+#define DISCOVER_MAX_UNITS   8
+#define DISCOVER_MAX_TARGETS 16
+#define DISCOVER_MAX_D       8
+
+typedef struct discover_ctx discover_ctx;
+
+/* Create a context bound to HIP device `device`.  *out receives the
+ * handle.  Errors: E_ARG (bad device or NULL out), E_HIP. */
+discover_status discover_create(int device, discover_ctx** out);
+
+/* Release the context and its workspace (NULL is ignored). */
+void discover_destroy(discover_ctx* ctx);
+
+/* Text of the last error on the calling thread; valid until the next call
+ * on this thread.  Never NULL. */
+const char* discover_last_error(void);
+
+/* One dataset.  Arrays of these form a batched call. */
+typedef struct {
+    int32_t n;                /* samples, >= 3 */
+    int32_t p;                /* primary features, 1..4096 */
+    int32_t T;                /* target / residual columns, 1..DISCOVER_MAX_TARGETS */
+    int32_t B;                /* base units, 0..DISCOVER_MAX_UNITS (0: dimensionless) */
+    const double* X;          /* device, feature-major: X[f * ldx + s] */
+    int64_t ldx;              /* >= n */
+    const double* Y;          /* device, Y[t * ldy + s] */
+    int64_t ldy;              /* >= n */
+    const int32_t* units;     /* host, units[f * B + b] integer exponents; NULL when B = 0 */
+    const int64_t* exclude;   /* device, IDs already in the subspace (their duplicate
+                                 groups are not selected again); may be NULL */
+    int32_t n_exclude;        /* entries in exclude, >= 0 */
+} discover_problem;
+
+/* Screening parameters (shared by every problem of a call). */
+typedef struct {
+    uint32_t ops;             /* enabled operators (DISCOVER_OP_* bits) */
+    int32_t rung;             /* R, 0..DISCOVER_MAX_RUNG */
+    uint32_t rung_ops[4];     /* rung_ops[r] (r = 1..R): operators of rung r; 0 = ops */
+    int32_t rung_pool[4];     /* rung_pool[r]: binary partners drawn from P_pool; -1 = r-1 */
+    int32_t k;                /* selected features per list, >= 1 */
+    int32_t score_mode;       /* DISCOVER_SCORE_PER_TARGET or DISCOVER_SCORE_MAX */
+    int32_t precision;        /* DISCOVER_FP64, DISCOVER_BF16_GUARD or DISCOVER_FP16_GUARD */
+    int32_t dedup;            /* 1: duplicate groups are merged (default); 0: off */
+} discover_screen_params;
+
+/* Per-problem counters of one screening call (host memory). */
+typedef struct {
+    int64_t n_raw;            /* |P_R|: every enumerated candidate */
+    int64_t n_unit_valid;     /* candidates passing the unit rules */
+    int64_t n_scored;         /* candidates with a finite, non-constant value vector */
+    int64_t pool_size;        /* candidates rescored exactly (summed over lists) */
+    int64_t pool_rounds;      /* pool enlargements needed (0 normally) */
+    int64_t n_merged;         /* duplicates merged into an earlier group */
+    int64_t n_selected;       /* selected features (summed over lists) */
+    double  max_lowprec_err;  /* precision forms: max |s_lowprec - s_fp64| over the pool */
+    double  guard_band;       /* precision forms: the guard half-width used */
+} discover_screen_stats;
+
+/* Enumerate the candidates of P_R (rungs 0..R), drop those failing the unit
+ * rules (add/sub need equal exponent vectors, exp/log a dimensionless
+ * argument, sqrt halves, sq doubles, inv negates, mul/div add/subtract
+ * exponents; a candidate with an invalid operand is invalid), evaluate
+ * every remaining candidate on the fly, and screen it by |Pearson r|
+ * against each target column (SIS of the cited SISSO method; Summary and
+ * Figure 1 caption).  A candidate is scored when all of its n values are
+ * finite and its standard deviation exceeds 1e-8 of its root-mean-square
+ * value.  Selection is exact: candidates ordered by (-score, ID);
+ * duplicates (|corr| >= 1 - 1e-9 with scores within 1e-9 relative) merge
+ * into one group represented by its smallest ID; groups containing an
+ * excluded ID are dropped; the first k groups are returned.
+ *
+ *   probs      host array of n_problems problem descriptions
+ *   prm        host, screening parameters
+ *   out_ids    device int64 [n_problems][T'][k], T' = T (PER_TARGET) or 1 (MAX);
+ *              ordered by (-score, ID); unused entries -1
+ *   out_scores device double, same shape: FP64 |r| (or max_t |r_t|); unused NaN
+ *   out_values device double [n_problems][T'][k][ldv] values of the selected
+ *              features, or NULL
+ *   ldv        >= max n when out_values is not NULL
+ *   out_stats  host, n_problems entries, or NULL
+ * Errors: E_ARG, E_NUMERIC (constant target), E_NOMEM, E_HIP,
+ * E_UNSUPPORTED (rung 3 without an operator-limited partner pool). */
+discover_status discover_generate_screen(discover_ctx* ctx, const discover_problem* probs,
+                                         int32_t n_problems, const discover_screen_params* prm,
+                                         int64_t* out_ids, double* out_scores,
+                                         double* out_values, int64_t ldv,
+                                         discover_screen_stats* out_stats, void* stream);
+
+/* One subspace for the sparsifying step. */
+typedef struct {
+    int32_t n;                /* samples */
+    int32_t S;                /* subspace rows, >= D */
+    const double* F;          /* device, F[row * ldf + s]: values of the subspace features */
+    int64_t ldf;              /* >= n */
+    const int64_t* ids;       /* device [S] candidate IDs of the rows (tie-breaks) */
+    const double* y;          /* device [n] target */
+} discover_l0_problem;
+
+typedef struct {
+    int64_t n_subsets;        /* C(S, D) */
+    int64_t n_band;           /* subsets refitted by Householder QR */
+    int64_t n_singular;       /* (informational) 0 when not counted */
+} discover_l0_stats;
+
+/* Exhaustive L0 (Eq. (1), Core Optimization Objective) with an intercept:
+ * every D-subset of the S rows is a support; its least-squares residual
+ * sum of squares RSS = ||y - beta0 - F_sub^T beta||^2.  Subsets whose
+ * normalized Cholesky pivot (centered, unit-norm columns, in row order)
+ * is <= 1e-10 are rank-deficient and skipped.  The scan uses the
+ * correlation matrix (per-thread Schur / Cholesky solves); every subset
+ * within 1e-7 (explained fraction) of the m-th best is refitted by FP64
+ * Householder QR on the raw data, and models are ranked by the QR RSS,
+ * values within 1e-11 ||y - mean||^2 counting as tied (smallest sorted
+ * candidate-ID tuple first).
+ *
+ *   D            1..3
+ *   m            models returned per problem, 1..64
+ *   out_subsets  device int32 [n_problems][m][D] row indices, ascending; -1 if absent
+ *   out_rmse     device double [n_problems][m] sqrt(RSS / n)
+ *   out_coef     device double [n_problems][m][D+1], intercept first, then the rows in
+ *                ascending order
+ *   out_resid    device double [n_problems][m][ldr] residuals y - prediction, or NULL
+ *   out_stats    host [n_problems] or NULL
+ * Errors: E_ARG, E_NUMERIC (constant y, or no non-singular subset), E_NOMEM, E_HIP. */
+discover_status discover_l0_fit(discover_ctx* ctx, const discover_l0_problem* probs,
+                                int32_t n_problems, int32_t D, int32_t m,
+                                int32_t* out_subsets, double* out_rmse, double* out_coef,
+                                double* out_resid, int64_t ldr,
+                                discover_l0_stats* out_stats, void* stream);
+
+/* Orthogonal matching pursuit (cited OMP, Software Description) over the
+ * rows of each problem: starting from init_active, repeatedly add the row
+ * with the largest |sum_s (f_s - mean f) r_s| / ||f - mean f|| (ties: the
+ * smaller candidate ID) and refit y on [1, active rows] by Householder QR,
+ * until D_max rows are active.
+ *
+ *   init_active  device int32 [n_problems][n_init] warm start (rows), or NULL (n_init = 0)
+ *   out_active   device int32 [n_problems][D_max] rows in order of addition
+ *   out_coef     device double [n_problems][D_max+1], intercept first, then the rows
+ *                in order of addition
+ *   out_rmse     device double [n_problems]
+ *   out_resid    device double [n_problems][ldr] or NULL
+ * Errors: E_ARG (D_max > S or D_max > DISCOVER_MAX_D), E_NOMEM, E_HIP. */
+discover_status discover_omp(discover_ctx* ctx, const discover_l0_problem* probs,
+                             int32_t n_problems, int32_t D_max,
+                             const int32_t* init_active, int32_t n_init,
+                             int32_t* out_active, double* out_coef, double* out_rmse,
+                             double* out_resid, int64_t ldr, void* stream);
+
+/* Number of raw candidates |P_R| of a search space (host only). */
+int64_t discover_count(int32_t p, const discover_screen_params* prm);
+
+/* Expression text of a candidate ID, e.g. "((x2 * x15) / x3)" (host only).
+ * Writes at most len bytes including the terminator.  E_ARG on a bad ID. */
+discover_status discover_decode(int32_t p, const discover_screen_params* prm, int64_t id,
+                                char* buf, size_t len);
+
+/* Kernel timing: when enabled, the named kernels are bracketed by HIP
+ * events on the stream they are launched on.  discover_timing reports the
+ * number of launches and the summed event time (ms) since the last reset
+ * for one kernel name ("screen_pairs", "l0_sweep", ...). */
+discover_status discover_set_timing(discover_ctx* ctx, int32_t enable);
+discover_status discover_timing(discover_ctx* ctx, const char* kernel, int64_t* launches,
+                                double* total_ms);
+discover_status discover_reset_timing(discover_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DISCOVER_H */

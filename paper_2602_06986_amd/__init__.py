@@ -1,0 +1,297 @@
+"""MI355X (gfx950) hot path of the DISCOVER / SISSO-style symbolic regression
+method (arXiv 2602.06986): candidate generation with unit pruning, SIS
+screening with exact top-k, exhaustive L0 and OMP.
+
+This module only marshals arguments to the C ABI of ``libdiscover.so``
+(include/discover.h); every step of the path runs in the library's HIP
+kernels.  PyTorch supplies device memory and the stream.  There is no CPU
+fallback: a missing library or GPU raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdiscover.so")
+
+OPS = ("exp", "log", "sqrt", "sq", "inv", "add", "sub", "mul", "div", "rdiv")
+OP_BIT = {name: 1 << i for i, name in enumerate(OPS)}
+SCORE_PER_TARGET, SCORE_MAX = 0, 1
+FP64, BF16_GUARD, FP16_GUARD = 0, 1, 2
+STATUS = {0: "OK", -1: "E_ARG", -2: "E_NOMEM", -3: "E_HIP", -4: "E_UNSUPPORTED",
+          -5: "E_NUMERIC", -6: "E_CAPACITY"}
+
+
+class DiscoverError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (STATUS.get(code, "?"), code, msg))
+        self.code = code
+
+
+class Problem(C.Structure):
+    _fields_ = [("n", C.c_int32), ("p", C.c_int32), ("T", C.c_int32), ("B", C.c_int32),
+                ("X", C.c_void_p), ("ldx", C.c_int64), ("Y", C.c_void_p), ("ldy", C.c_int64),
+                ("units", C.c_void_p), ("exclude", C.c_void_p), ("n_exclude", C.c_int32)]
+
+
+class ScreenParams(C.Structure):
+    _fields_ = [("ops", C.c_uint32), ("rung", C.c_int32), ("rung_ops", C.c_uint32 * 4),
+                ("rung_pool", C.c_int32 * 4), ("k", C.c_int32), ("score_mode", C.c_int32),
+                ("precision", C.c_int32), ("dedup", C.c_int32)]
+
+
+class ScreenStats(C.Structure):
+    _fields_ = [("n_raw", C.c_int64), ("n_unit_valid", C.c_int64), ("n_scored", C.c_int64),
+                ("pool_size", C.c_int64), ("pool_rounds", C.c_int64), ("n_merged", C.c_int64),
+                ("n_selected", C.c_int64), ("max_lowprec_err", C.c_double),
+                ("guard_band", C.c_double)]
+
+    def asdict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class L0Problem(C.Structure):
+    _fields_ = [("n", C.c_int32), ("S", C.c_int32), ("F", C.c_void_p), ("ldf", C.c_int64),
+                ("ids", C.c_void_p), ("y", C.c_void_p)]
+
+
+class L0Stats(C.Structure):
+    _fields_ = [("n_subsets", C.c_int64), ("n_band", C.c_int64), ("n_singular", C.c_int64)]
+
+    def asdict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+# Every symbol include/discover.h declares.
+SYMBOLS = ("discover_create", "discover_destroy", "discover_last_error",
+           "discover_generate_screen", "discover_l0_fit", "discover_omp", "discover_count",
+           "discover_decode", "discover_set_timing", "discover_timing", "discover_reset_timing")
+
+_lib = None
+
+
+def lib():
+    """Load libdiscover.so (built in-tree by paper_2602_06986_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libdiscover.so is not built; run python -m paper_2602_06986_amd.build")
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        L.discover_create.argtypes = [C.c_int, C.POINTER(P)]
+        L.discover_destroy.argtypes = [P]
+        L.discover_destroy.restype = None
+        L.discover_last_error.restype = C.c_char_p
+        L.discover_generate_screen.argtypes = [P, C.POINTER(Problem), C.c_int32,
+                                               C.POINTER(ScreenParams), P, P, P, C.c_int64,
+                                               C.POINTER(ScreenStats), P]
+        L.discover_l0_fit.argtypes = [P, C.POINTER(L0Problem), C.c_int32, C.c_int32, C.c_int32,
+                                      P, P, P, P, C.c_int64, C.POINTER(L0Stats), P]
+        L.discover_omp.argtypes = [P, C.POINTER(L0Problem), C.c_int32, C.c_int32, P, C.c_int32,
+                                   P, P, P, P, C.c_int64, P]
+        L.discover_count.argtypes = [C.c_int32, C.POINTER(ScreenParams)]
+        L.discover_count.restype = C.c_int64
+        L.discover_decode.argtypes = [C.c_int32, C.POINTER(ScreenParams), C.c_int64, C.c_char_p,
+                                      C.c_size_t]
+        L.discover_set_timing.argtypes = [P, C.c_int32]
+        L.discover_timing.argtypes = [P, C.c_char_p, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
+        L.discover_reset_timing.argtypes = [P]
+        _lib = L
+    return _lib
+
+
+def _check(code):
+    if code != 0:
+        raise DiscoverError(code, lib().discover_last_error().decode())
+
+
+def params(ops=OPS, rung=1, k=20, score_mode=SCORE_PER_TARGET, precision=FP64, dedup=True,
+           rung_ops=None, rung_pool=None):
+    """Build the screening parameter struct from operator names."""
+    prm = ScreenParams()
+    prm.ops = sum(OP_BIT[o] for o in ops)
+    prm.rung = rung
+    for r in range(4):
+        ro = rung_ops[r] if rung_ops is not None and r < len(rung_ops) else None
+        prm.rung_ops[r] = 0 if ro is None else sum(OP_BIT[o] for o in ro)
+        rp = rung_pool[r] if rung_pool is not None and r < len(rung_pool) else None
+        prm.rung_pool[r] = -1 if rp is None else int(rp)
+    prm.k = k
+    prm.score_mode = score_mode
+    prm.precision = precision
+    prm.dedup = 1 if dedup else 0
+    return prm
+
+
+def count(p, prm):
+    v = lib().discover_count(p, C.byref(prm))
+    if v < 0:
+        _check(int(v))
+    return int(v)
+
+
+def decode(p, prm, cid):
+    buf = C.create_string_buffer(4096)
+    _check(lib().discover_decode(p, C.byref(prm), int(cid), buf, 4096))
+    return buf.value.decode()
+
+
+def _stream_handle(torch, device):
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Context:
+    """One library context on one HIP device."""
+
+    def __init__(self, device=0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible: the discover library has no CPU path")
+        self.torch = torch
+        self.device = device
+        self.h = C.c_void_p()
+        _check(lib().discover_create(device, C.byref(self.h)))
+
+    def close(self):
+        if self.h:
+            lib().discover_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ timing
+    def set_timing(self, on=True):
+        _check(lib().discover_set_timing(self.h, 1 if on else 0))
+
+    def reset_timing(self):
+        _check(lib().discover_reset_timing(self.h))
+
+    def timing(self, kernel):
+        n = C.c_int64()
+        ms = C.c_double()
+        _check(lib().discover_timing(self.h, kernel.encode(), C.byref(n), C.byref(ms)))
+        return int(n.value), float(ms.value)
+
+    # ------------------------------------------------------------ calls
+    def generate_screen(self, X, Y, prm, units=None, exclude=None, values=True):
+        """X [p][n], Y [T][n] float64 CUDA tensors; units [p][B] int32 host
+        array or None; exclude int64 CUDA tensor of IDs or None.
+        Returns (ids [T'][k], scores [T'][k], values [T'][k][n] or None, stats)."""
+        torch = self.torch
+        import numpy as np
+        X = X.contiguous()
+        Y = Y.contiguous()
+        p, n = X.shape
+        T = Y.shape[0]
+        Tl = 1 if prm.score_mode == SCORE_MAX else T
+        dev = X.device
+        ids = torch.empty((Tl, prm.k), dtype=torch.int64, device=dev)
+        sc = torch.empty((Tl, prm.k), dtype=torch.float64, device=dev)
+        vals = torch.empty((Tl, prm.k, n), dtype=torch.float64, device=dev) if values else None
+        pb = Problem()
+        pb.n, pb.p, pb.T = n, p, T
+        u = None
+        if units is not None:
+            u = np.ascontiguousarray(units, dtype=np.int32)
+            pb.B = u.shape[1]
+            pb.units = u.ctypes.data
+        else:
+            pb.B = 0
+        pb.X, pb.ldx = X.data_ptr(), n
+        pb.Y, pb.ldy = Y.data_ptr(), n
+        if exclude is not None and exclude.numel():
+            exclude = exclude.contiguous()
+            pb.exclude, pb.n_exclude = exclude.data_ptr(), exclude.numel()
+        st = ScreenStats()
+        _check(lib().discover_generate_screen(
+            self.h, C.byref(pb), 1, C.byref(prm), ids.data_ptr(), sc.data_ptr(),
+            vals.data_ptr() if vals is not None else None, n, C.byref(st),
+            _stream_handle(torch, dev)))
+        return ids, sc, vals, st.asdict()
+
+    def l0_fit(self, F, ids, y, D, m=1, resid=True):
+        """F [S][n] float64, ids [S] int64, y [n] float64 (CUDA).  Returns
+        (subsets [m][D] rows, rmse [m], coef [m][D+1], resid [m][n], stats)."""
+        torch = self.torch
+        F = F.contiguous()
+        S, n = F.shape
+        dev = F.device
+        sub = torch.empty((m, D), dtype=torch.int32, device=dev)
+        rmse = torch.empty(m, dtype=torch.float64, device=dev)
+        coef = torch.empty((m, D + 1), dtype=torch.float64, device=dev)
+        res = torch.empty((m, n), dtype=torch.float64, device=dev) if resid else None
+        pb = L0Problem()
+        pb.n, pb.S, pb.F, pb.ldf = n, S, F.data_ptr(), n
+        ids = ids.contiguous()
+        y = y.contiguous()
+        pb.ids, pb.y = ids.data_ptr(), y.data_ptr()
+        st = L0Stats()
+        _check(lib().discover_l0_fit(self.h, C.byref(pb), 1, D, m, sub.data_ptr(),
+                                     rmse.data_ptr(), coef.data_ptr(),
+                                     res.data_ptr() if res is not None else None, n,
+                                     C.byref(st), _stream_handle(torch, dev)))
+        return sub, rmse, coef, res, st.asdict()
+
+    def omp(self, F, ids, y, D_max, init=None):
+        """OMP over the rows of F from the warm start ``init`` (int32 CUDA
+        tensor of rows, or None).  Returns (active [D_max], coef [D_max+1],
+        rmse, resid [n])."""
+        torch = self.torch
+        F = F.contiguous()
+        S, n = F.shape
+        dev = F.device
+        act = torch.empty(D_max, dtype=torch.int32, device=dev)
+        coef = torch.empty(D_max + 1, dtype=torch.float64, device=dev)
+        rmse = torch.empty(1, dtype=torch.float64, device=dev)
+        res = torch.empty(n, dtype=torch.float64, device=dev)
+        pb = L0Problem()
+        ids = ids.contiguous()
+        y = y.contiguous()
+        pb.n, pb.S, pb.F, pb.ldf, pb.ids, pb.y = n, S, F.data_ptr(), n, ids.data_ptr(), y.data_ptr()
+        n_init = 0
+        ip = None
+        if init is not None and init.numel():
+            init = init.to(torch.int32).contiguous()
+            n_init = init.numel()
+            ip = init.data_ptr()
+        _check(lib().discover_omp(self.h, C.byref(pb), 1, D_max, ip, n_init, act.data_ptr(),
+                                  coef.data_ptr(), rmse.data_ptr(), res.data_ptr(), n,
+                                  _stream_handle(torch, dev)))
+        return act, coef, rmse, res
+
+    # ------------------------------------------------------------ loop
+    def sisso(self, X, y, prm, D, units=None, n_resid=1, omp_D=0):
+        """The SISSO loop: for d = 1..D screen against the residual(s) of the
+        best dimension-(d-1) model(s) (the target at d = 1), append the k
+        selected features to the subspace, and fit the original y by
+        exhaustive L0 over all d-subsets.  Optionally extend the D-model by
+        OMP to omp_D features.  X [p][n], y [n] CUDA float64."""
+        torch = self.torch
+        dev = X.device
+        S_ids = torch.zeros(0, dtype=torch.int64, device=dev)
+        F = torch.zeros((0, X.shape[1]), dtype=torch.float64, device=dev)
+        targets = y.reshape(1, -1)
+        dims = []
+        for d in range(1, D + 1):
+            q = ScreenParams.from_buffer_copy(prm)
+            if targets.shape[0] > 1:
+                q.score_mode = SCORE_MAX
+            ids, sc, vals, st = self.generate_screen(X, targets, q, units=units, exclude=S_ids)
+            ok = ids[0] >= 0
+            S_ids = torch.cat([S_ids, ids[0][ok]])
+            F = torch.cat([F, vals[0][ok]])
+            m = n_resid
+            sub, rmse, coef, res, l0st = self.l0_fit(F, S_ids, y, d, m)
+            dims.append({"sel_ids": ids[0], "sel_scores": sc[0], "screen_stats": st,
+                         "subsets": sub, "rmse": rmse, "coef": coef, "l0_stats": l0st})
+            targets = res
+        out = {"dims": dims, "S_ids": S_ids, "F": F}
+        if omp_D > D:
+            act, coef, rmse, res = self.omp(F, S_ids, y, omp_D, dims[-1]["subsets"][0])
+            out["omp"] = {"active": act, "coef": coef, "rmse": rmse, "resid": res}
+        return out

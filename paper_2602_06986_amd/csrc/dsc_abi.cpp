@@ -1,0 +1,126 @@
+// Context lifetime, error text, host-side space queries and kernel timing.
+#include "dsc_space.h"
+
+extern "C" discover_status discover_create(int device, discover_ctx** out) {
+    using namespace dsc;
+    return guarded([&] {
+        DSC_REQUIRE(out, "out is NULL");
+        *out = nullptr;
+        int count = 0;
+        DSC_HIP(hipGetDeviceCount(&count));
+        DSC_REQUIRE(device >= 0 && device < count, "device %d outside 0..%d", device, count - 1);
+        DSC_HIP(hipSetDevice(device));
+        discover_ctx* c = new discover_ctx();
+        c->device = device;
+        *out = c;
+    });
+}
+
+extern "C" void discover_destroy(discover_ctx* ctx) {
+    if (!ctx) return;
+    if (hipSetDevice(ctx->device) == hipSuccess) {
+        if (hipDeviceSynchronize() != hipSuccess) { /* keep tearing down */ }
+        for (auto& kv : ctx->bufs)
+            if (kv.second.p && hipFree(kv.second.p) != hipSuccess) { /* ignore */ }
+        for (auto& p : ctx->pending) {
+            if (hipEventDestroy(p.a) != hipSuccess || hipEventDestroy(p.b) != hipSuccess) { }
+        }
+        for (hipEvent_t e : ctx->free_events)
+            if (hipEventDestroy(e) != hipSuccess) { }
+    }
+    delete ctx;
+}
+
+extern "C" const char* discover_last_error(void) { return dsc::get_error(); }
+
+extern "C" int64_t discover_count(int32_t p, const discover_screen_params* prm) {
+    using namespace dsc;
+    int64_t out = -1;
+    discover_status s = guarded([&] {
+        DSC_REQUIRE(prm && p >= 1, "prm/p");
+        DSC_REQUIRE(prm->rung >= 0 && prm->rung <= DISCOVER_MAX_RUNG, "rung");
+        SpaceDev d{};
+        Space sp;
+        discover_screen_params q = *prm;
+        // counting needs no operand plan: build the layout only
+        d.p = p;
+        d.R = q.rung;
+        d.L[0] = p;
+        d.off[1] = p;
+        for (int r = 1; r <= d.R; r++) {
+            const uint32_t m = (q.rung_ops[r] ? q.rung_ops[r] : q.ops) & DISCOVER_OPS_ALL;
+            const int pool = q.rung_pool[r] < 0 ? r - 1 : q.rung_pool[r];
+            DSC_REQUIRE(pool <= r - 1, "rung_pool");
+            const int64_t np = pool == r - 1 ? choose2(d.off[r]) - choose2(d.off[r - 1])
+                                             : d.L[r - 1] * d.off[pool + 1];
+            int64_t L = 0;
+            for (int o = 0; o < 10; o++)
+                if (m >> o & 1u) L += o < OP_ADD ? d.L[r - 1] : np;
+            d.L[r] = L;
+            d.off[r + 1] = d.off[r] + L;
+        }
+        out = d.off[d.R + 1];
+        (void)sp;
+    });
+    return s == DISCOVER_OK ? out : (int64_t)s;
+}
+
+extern "C" discover_status discover_decode(int32_t p, const discover_screen_params* prm, int64_t id,
+                                           char* buf, size_t len) {
+    using namespace dsc;
+    return guarded([&] {
+        DSC_REQUIRE(prm && buf && len > 0, "prm/buf/len");
+        const int64_t N = discover_count(p, prm);
+        DSC_REQUIRE(N > 0 && id >= 0 && id < N, "id %lld outside the space", (long long)id);
+        // layout only (operand plan not needed): mirror build_space's block table
+        SpaceDev d{};
+        d.p = p;
+        d.R = prm->rung;
+        d.L[0] = p;
+        d.off[1] = p;
+        for (int o = 0; o < 10; o++) d.block[0][o] = -1;
+        for (int r = 1; r <= d.R; r++) {
+            d.ops[r] = (prm->rung_ops[r] ? prm->rung_ops[r] : prm->ops) & DISCOVER_OPS_ALL;
+            d.pool[r] = prm->rung_pool[r] < 0 ? r - 1 : prm->rung_pool[r];
+            d.npairs[r] = d.pool[r] == r - 1 ? choose2(d.off[r]) - choose2(d.off[r - 1])
+                                              : d.L[r - 1] * d.off[d.pool[r] + 1];
+            int64_t at = d.off[r];
+            for (int o = 0; o < 10; o++) {
+                if (!(d.ops[r] >> o & 1u)) { d.block[r][o] = -1; continue; }
+                d.block[r][o] = at;
+                at += o < OP_ADD ? d.L[r - 1] : d.npairs[r];
+            }
+            d.L[r] = at - d.off[r];
+            d.off[r + 1] = at;
+        }
+        const std::string s = expr_of(d, id);
+        std::snprintf(buf, len, "%s", s.c_str());
+    });
+}
+
+extern "C" discover_status discover_set_timing(discover_ctx* ctx, int32_t enable) {
+    using namespace dsc;
+    return guarded([&] {
+        DSC_REQUIRE(ctx, "ctx is NULL");
+        ctx->timing = enable != 0;
+    });
+}
+
+extern "C" discover_status discover_timing(discover_ctx* ctx, const char* kernel, int64_t* launches,
+                                           double* total_ms) {
+    using namespace dsc;
+    return guarded([&] {
+        DSC_REQUIRE(ctx && kernel && launches && total_ms, "arguments");
+        auto it = ctx->times.find(kernel);
+        *launches = it == ctx->times.end() ? 0 : it->second.first;
+        *total_ms = it == ctx->times.end() ? 0.0 : it->second.second;
+    });
+}
+
+extern "C" discover_status discover_reset_timing(discover_ctx* ctx) {
+    using namespace dsc;
+    return guarded([&] {
+        DSC_REQUIRE(ctx, "ctx is NULL");
+        ctx->times.clear();
+    });
+}

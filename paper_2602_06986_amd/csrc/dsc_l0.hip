@@ -1,0 +1,778 @@
+// Sparsifying step on gfx950: exhaustive L0 over all D-subsets of a
+// subspace (Eq. (1), Core Optimization Objective, with an intercept) and
+// orthogonal matching pursuit (cited OMP, Software Description).
+//
+// L0 plan per problem:
+//   1. Z = centered, unit-norm rows of F and of y (row S) -> Gram G = Z Z^T
+//      ((S+1) x (S+1) FP64; G[a][S] is the correlation of row a with y).
+//   2. Sweep: every D-subset's explained fraction q = c^T C^{-1} c from G by
+//      per-lane Schur/Cholesky updates (D = 3: one wave per (a, 64 c's),
+//      looping over b; uniform per-(a, b) factors staged in LDS).  Each wave
+//      keeps only its best q (b packed into the low mantissa bits).
+//   3. thr = m-th largest wave best - DELTA; waves whose best reaches thr
+//      are swept again and every subset with q >= thr is collected.
+//   4. The collected band is refitted by FP64 Householder QR on the raw
+//      data (one workgroup per subset) and ranked by RSS with the tie rule.
+#include "dsc_select.h"
+
+namespace dsc {
+
+constexpr double PIV_TOL = 1e-10;     // normalized Cholesky pivot at/below which a subset is singular
+constexpr double GRAM_DELTA = 1e-7;   // band width in explained fraction
+constexpr double TAU_TIE = 1e-11;     // RSS tie tolerance relative to ||y - mean||^2
+
+// ------------------------------------------------------------------ prep
+// One wave per row (rows 0..S-1 of F, row S = y): Z = (f - mean) / ||f - mean||.
+__global__ __launch_bounds__(256) void k_l0_prep(int n, int S, const double* __restrict__ F,
+                                                 int64_t ldf, const double* __restrict__ y,
+                                                 int ldz, double* __restrict__ Z,
+                                                 double* __restrict__ yy) {
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row > S) return;
+    const double* f = row < S ? F + (int64_t)row * ldf : y;
+    double s = 0.0;
+    for (int i = lane; i < n; i += 64) s += f[i];
+    const double m = wave_sum(s) / n;
+    double q = 0.0;
+    for (int i = lane; i < n; i += 64) {
+        const double d = f[i] - m;
+        q += d * d;
+    }
+    q = wave_sum(q);
+    const double inv = q > 0.0 ? 1.0 / sqrt(q) : 0.0;
+    double* z = Z + (int64_t)row * ldz;
+    for (int i = lane; i < ldz; i += 64) z[i] = i < n ? (f[i] - m) * inv : 0.0;
+    if (row == S && lane == 0) *yy = q;
+}
+
+// G = Z Z^T for (S+1) rows, 64x64 tiles, 4x4 outputs per thread, samples
+// staged through LDS in chunks of 16.
+__global__ __launch_bounds__(256) void k_gram(int M, int ldz, int nk, const double* __restrict__ Z,
+                                              double* __restrict__ G, int ldg) {
+    __shared__ double As[16][65], Bs[16][65];
+    const int bi = blockIdx.y * 64, bj = blockIdx.x * 64;
+    if (bj + 63 < bi) return;                 // lower triangle mirrored below
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    double acc[4][4] = {};
+    for (int k0 = 0; k0 < nk; k0 += 16) {
+        for (int e = threadIdx.x; e < 16 * 64; e += 256) {
+            const int r = e >> 4, kk = e & 15;
+            const int ra = bi + r, rb = bj + r;
+            As[kk][r] = ra < M ? Z[(int64_t)ra * ldz + k0 + kk] : 0.0;
+            Bs[kk][r] = rb < M ? Z[(int64_t)rb * ldz + k0 + kk] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 16; kk++) {
+            double a[4], b[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                a[u] = As[kk][ty * 4 + u];
+                b[u] = Bs[kk][tx * 4 + u];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; u++)
+#pragma unroll
+                for (int v = 0; v < 4; v++) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < 4; u++)
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+            const int i = bi + ty * 4 + u, j = bj + tx * 4 + v;
+            if (i < M && j < M && i <= j) {
+                G[(int64_t)i * ldg + j] = acc[u][v];
+                G[(int64_t)j * ldg + i] = acc[u][v];
+            }
+        }
+}
+
+// ----------------------------------------------------------------- sweep
+struct SweepArgs {
+    const double* G;
+    int ldg, S, D;
+    const int2* items;        // (a, first c / b / a of the 64-lane block)
+    int64_t n_items;
+    double* wbest;            // per item: best packed q (or -1)
+    int32_t* wlane;           // per item: the lane index of the best
+    // collect mode
+    double thr;
+    int4* band;               // (a, b, c, -) rows
+    double* bq;
+    unsigned long long* bcnt;
+    int64_t bcap;
+};
+
+__device__ __forceinline__ double pack_q(double q, int b) {
+    unsigned long long u = (unsigned long long)__double_as_longlong(q);
+    u = (u & ~0xFFFFull) | (unsigned long long)(b & 0xFFFF);
+    return __longlong_as_double((long long)u);
+}
+
+__device__ __forceinline__ double fast_rcp(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    const double e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+template <bool COLLECT>
+__device__ __forceinline__ void wave_finish(const SweepArgs& g, int64_t item, double best,
+                                            int lane) {
+    if (COLLECT) return;
+    const double mx = wave_max(best);
+    const unsigned long long hit = __ballot(best == mx);
+    const int who = __ffsll((long long)hit) - 1;
+    if (lane == 0) {
+        g.wbest[item] = mx;
+        g.wlane[item] = who;
+    }
+}
+
+__device__ __forceinline__ void band_push(const SweepArgs& g, int a, int b, int c, double q) {
+    const unsigned long long slot = atomicAdd(g.bcnt, 1ull);
+    if ((int64_t)slot < g.bcap) {
+        g.band[slot] = make_int4(a, b, c, 0);
+        g.bq[slot] = q;
+    }
+}
+
+// D = 1: lane a.
+template <bool COLLECT>
+__global__ __launch_bounds__(256) void k_sweep1(SweepArgs g) {
+    const int64_t it = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (it >= g.n_items) return;
+    const int lane = threadIdx.x & 63;
+    const int a = g.items[it].y + lane;
+    double q = -1.0;
+    if (a < g.S) {
+        const double caa = g.G[(int64_t)a * g.ldg + a], ca = g.G[(int64_t)a * g.ldg + g.S];
+        if (caa > PIV_TOL) q = ca * ca / caa;
+    }
+    if (COLLECT) {
+        if (q >= g.thr) band_push(g, a, -1, -1, q);
+        return;
+    }
+    wave_finish<COLLECT>(g, it, q, lane);
+}
+
+// D = 2: fixed a per wave, lane b.
+template <bool COLLECT>
+__global__ __launch_bounds__(256) void k_sweep2(SweepArgs g) {
+    const int64_t it = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (it >= g.n_items) return;
+    const int lane = threadIdx.x & 63;
+    const int a = g.items[it].x, b = g.items[it].y + lane;
+    const double* Ga = g.G + (int64_t)a * g.ldg;
+    const double caa = Ga[a], ca = Ga[g.S];
+    double q = -1.0;
+    if (b < g.S && b > a && caa > PIV_TOL) {
+        const double cab = Ga[b], cbb = g.G[(int64_t)b * g.ldg + b], cb = g.G[(int64_t)b * g.ldg + g.S];
+        const double w = cab / caa;
+        const double piv = cbb - cab * w;
+        const double e = cb - ca * w;
+        if (piv > PIV_TOL) q = ca * ca / caa + e * e / piv;
+    }
+    if (COLLECT) {
+        if (q >= g.thr) band_push(g, a, b, -1, q);
+        return;
+    }
+    wave_finish<COLLECT>(g, it, q, lane);
+}
+
+// D = 3: fixed a per workgroup (4 waves = 4 consecutive c-blocks of 64),
+// lane c, loop over a < b < c.  Per b (uniform): u_b = G[a][b],
+// g_b = z'_b / d_b, h_b = 1 / d_b, Q_ab = c_a^2/G_aa + z'_b^2 / d_b with
+// d_b = G_bb - u_b^2 / G_aa and z'_b = c_b - u_b c_a / G_aa.  Per subset:
+//   C'  = G[b][c] - u_b u_c / G_aa
+//   den = d_c - C'^2 / d_b            (third Cholesky pivot)
+//   e   = z'_c - C' g_b
+//   q   = Q_ab + e^2 / den.
+constexpr int SW3_CHUNK = 1024;       // b entries staged in LDS at a time (32 KB)
+
+template <bool COLLECT>
+__global__ __launch_bounds__(256) void k_sweep3(SweepArgs g) {
+    __shared__ double4 tab[SW3_CHUNK];
+    const int64_t it0 = (int64_t)blockIdx.x * 4;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t it = it0 + wv;
+    // the 4 waves of a block share a (items are grouped by a on the host)
+    const int a = g.items[min(it0, g.n_items - 1)].x;
+    const double* Ga = g.G + (int64_t)a * g.ldg;
+    const double caa = Ga[a], ca = Ga[g.S];
+    const double ica = 1.0 / caa;
+    int cmax_blk = a + 1;
+    for (int w = 0; w < 4; w++)
+        if (it0 + w < g.n_items && g.items[it0 + w].x == a)
+            cmax_blk = max(cmax_blk, min(g.S, g.items[it0 + w].y + 64));
+    const bool active = it < g.n_items && g.items[it].x == a && caa > PIV_TOL;
+    const int c0 = active ? g.items[it].y : g.S;
+    const int c = c0 + lane;
+    const bool cok = active && c < g.S;
+    const int cc = cok ? c : a;
+    const double uc = Ga[cc];
+    const double upc = uc * ica;
+    const double dc = g.G[(int64_t)cc * g.ldg + cc] - uc * upc;
+    const double zc = g.G[(int64_t)cc * g.ldg + g.S] - ca * upc;
+    const int bend = active ? min(g.S, c0 + 64) - 1 : a + 1;   // b < (largest c of the wave)
+    const double* colc = g.G + cc;
+    double best = -1.0;
+    for (int b0 = a + 1; b0 < cmax_blk - 1; b0 += SW3_CHUNK) {
+        const int nb = min(SW3_CHUNK, cmax_blk - 1 - b0);
+        __syncthreads();
+        for (int t = threadIdx.x; t < nb; t += 256) {
+            const int b = b0 + t;
+            const double ub = Ga[b];
+            const double db = g.G[(int64_t)b * g.ldg + b] - ub * ub * ica;
+            const double zb = g.G[(int64_t)b * g.ldg + g.S] - ub * ca * ica;
+            double4 e;
+            if (db > PIV_TOL) {
+                const double hb = 1.0 / db;
+                e = make_double4(ub, zb * hb, hb, ca * ca * ica + zb * zb * hb);
+            } else {
+                e = make_double4(ub, 0.0, 0.0, -1.0);     // singular pair: skipped
+            }
+            tab[t] = e;
+        }
+        __syncthreads();
+        const int bl = min(b0 + nb, bend);
+        for (int b = b0; b < bl; b++) {
+            const double4 e = tab[b - b0];
+            if (e.w < 0.0) continue;                      // uniform: singular (a, b)
+            const double Cbc = colc[(int64_t)b * g.ldg];
+            const double Cp = fma(-e.x, upc, Cbc);
+            const double ee = fma(-Cp, e.y, zc);
+            const double t = Cp * e.z;
+            const double den = fma(-Cp, t, dc);
+            double q = fma(ee * ee, fast_rcp(den), e.w);
+            const bool ok = cok && (b < c) && (den > PIV_TOL);
+            if (COLLECT) {
+                if (ok && q >= g.thr) band_push(g, a, b, c, q);
+            } else {
+                q = ok ? pack_q(q, b) : -1.0;
+                best = fmax(best, q);
+            }
+        }
+    }
+    if (it < g.n_items) wave_finish<COLLECT>(g, it, best, lane);
+}
+
+// ------------------------------------------------------------ QR refit
+// Least squares of y on [1, F rows idx[0..d-1]] by Householder QR, one
+// 256-thread workgroup, matrix in a global scratch slab of (d+2) columns.
+__device__ double block_sum256(double v, double* red) {
+    v = wave_sum(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__device__ void block_lsq(int n, int d, const int* idx, const double* __restrict__ F, int64_t ldf,
+                          const double* __restrict__ y, double* A, double* coef, double* rss,
+                          double* resid) {
+    __shared__ double red[4];
+    __shared__ double R[DISCOVER_MAX_D + 1][DISCOVER_MAX_D + 2];
+    const int m = d + 1;
+    double* w = A + (int64_t)m * n;
+    for (int i = threadIdx.x; i < n; i += 256) {
+        A[i] = 1.0;
+        for (int j = 0; j < d; j++) A[(int64_t)(j + 1) * n + i] = F[(int64_t)idx[j] * ldf + i];
+        w[i] = y[i];
+    }
+    __syncthreads();
+    for (int j = 0; j < m; j++) {
+        double* aj = A + (int64_t)j * n;
+        double loc = 0.0;
+        for (int i = j + threadIdx.x; i < n; i += 256) loc += aj[i] * aj[i];
+        const double nrm = sqrt(block_sum256(loc, red));
+        const double ajj = aj[j];
+        const double alpha = ajj > 0 ? -nrm : nrm;
+        const double v0 = ajj - alpha;
+        const double vv = 2.0 * nrm * (nrm + fabs(ajj));   // v^T v
+        __syncthreads();
+        if (threadIdx.x == 0) aj[j] = v0;
+        __syncthreads();
+        for (int c = j + 1; c <= m; c++) {            // column m is the right-hand side
+            double* ac = c < m ? A + (int64_t)c * n : w;
+            double dl = 0.0;
+            for (int i = j + threadIdx.x; i < n; i += 256) dl += aj[i] * ac[i];
+            const double dot = block_sum256(dl, red);
+            const double gm = vv > 0.0 ? 2.0 * dot / vv : 0.0;
+            for (int i = j + threadIdx.x; i < n; i += 256) ac[i] -= gm * aj[i];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            R[j][j] = alpha;
+            for (int c = j + 1; c < m; c++) R[j][c] = A[(int64_t)c * n + j];
+            R[j][m] = w[j];
+        }
+        __syncthreads();
+    }
+    double loc = 0.0;
+    for (int i = m + threadIdx.x; i < n; i += 256) loc += w[i] * w[i];
+    const double r2 = block_sum256(loc, red);
+    if (threadIdx.x == 0) {
+        for (int j = m - 1; j >= 0; j--) {
+            double acc = R[j][m];
+            for (int c = j + 1; c < m; c++) acc -= R[j][c] * coef[c];
+            coef[j] = acc / R[j][j];
+        }
+        *rss = r2;
+    }
+    __syncthreads();
+    if (resid) {
+        for (int i = threadIdx.x; i < n; i += 256) {
+            double p = coef[0];
+            for (int j = 0; j < d; j++) p = fma(coef[j + 1], F[(int64_t)idx[j] * ldf + i], p);
+            resid[i] = y[i] - p;
+        }
+    }
+}
+
+// One workgroup per band entry (persistent over the band).
+__global__ __launch_bounds__(256) void k_refit(int n, int D, const double* __restrict__ F,
+                                               int64_t ldf, const double* __restrict__ y,
+                                               const int4* __restrict__ band, int64_t nb,
+                                               double* __restrict__ scratch,
+                                               double* __restrict__ brss,
+                                               double* __restrict__ bcoef) {
+    __shared__ double coef[DISCOVER_MAX_D + 1];
+    __shared__ double rss;
+    double* A = scratch + (int64_t)blockIdx.x * (D + 2) * n;
+    for (int64_t e = blockIdx.x; e < nb; e += gridDim.x) {
+        const int4 s = band[e];
+        const int idx[3] = {s.x, s.y, s.z};
+        block_lsq(n, D, idx, F, ldf, y, A, coef, &rss, nullptr);
+        if (threadIdx.x == 0) {
+            brss[e] = rss;
+            for (int j = 0; j <= D; j++) bcoef[e * (D + 1) + j] = coef[j];
+        }
+        __syncthreads();
+    }
+}
+
+// Rank the band (one thread): repeatedly take the minimum RSS; entries
+// within TAU_TIE * yy of it are tied and the smallest sorted-ID tuple wins.
+__global__ void k_rank_models(const int4* __restrict__ band, const double* __restrict__ brss,
+                              const double* __restrict__ bcoef, int64_t nb, int D, int m,
+                              const int64_t* __restrict__ ids, const double* __restrict__ yyp,
+                              int n, uint8_t* __restrict__ taken, int32_t* __restrict__ out_sub,
+                              double* __restrict__ out_rmse, double* __restrict__ out_coef,
+                              int32_t* __restrict__ chosen) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double yy = *yyp;
+    for (int64_t e = 0; e < nb; e++) taken[e] = !(brss[e] >= 0.0);
+    for (int q = 0; q < m; q++) {
+        double rmin = INFINITY;
+        for (int64_t e = 0; e < nb; e++)
+            if (!taken[e] && brss[e] < rmin) rmin = brss[e];
+        int64_t pick = -1;
+        int64_t key[3] = {0, 0, 0}, bk[3] = {0, 0, 0};
+        if (rmin < INFINITY) {
+            for (int64_t e = 0; e < nb; e++) {
+                if (taken[e] || !(brss[e] <= rmin + TAU_TIE * yy)) continue;
+                const int4 s = band[e];
+                const int pos[3] = {s.x, s.y, s.z};
+                for (int j = 0; j < D; j++) key[j] = ids[pos[j]];
+                for (int u = 1; u < D; u++)          // sort the ID tuple
+                    for (int v = u; v > 0 && key[v - 1] > key[v]; v--) {
+                        const int64_t tt = key[v]; key[v] = key[v - 1]; key[v - 1] = tt;
+                    }
+                bool better = pick < 0;
+                for (int j = 0; j < D && !better; j++) {
+                    if (key[j] < bk[j]) { better = true; break; }
+                    if (key[j] > bk[j]) break;
+                }
+                if (better) {
+                    pick = e;
+                    for (int j = 0; j < D; j++) bk[j] = key[j];
+                }
+            }
+        }
+        chosen[q] = (int32_t)pick;
+        if (pick < 0) {
+            for (int j = 0; j < D; j++) out_sub[q * D + j] = -1;
+            out_rmse[q] = __longlong_as_double(0x7FF8000000000000LL);
+            for (int j = 0; j <= D; j++) out_coef[q * (D + 1) + j] = __longlong_as_double(0x7FF8000000000000LL);
+            continue;
+        }
+        taken[pick] = 1;
+        const int4 s = band[pick];
+        const int pos[3] = {s.x, s.y, s.z};
+        for (int j = 0; j < D; j++) out_sub[q * D + j] = pos[j];
+        out_rmse[q] = sqrt(brss[pick] / n);
+        for (int j = 0; j <= D; j++) out_coef[q * (D + 1) + j] = bcoef[pick * (D + 1) + j];
+    }
+}
+
+// Residuals of the chosen models: one block per model.
+__global__ __launch_bounds__(256) void k_resid(int n, int D, const double* __restrict__ F,
+                                               int64_t ldf, const double* __restrict__ y,
+                                               const int32_t* __restrict__ sub,
+                                               const double* __restrict__ coef,
+                                               double* __restrict__ out, int64_t ldr) {
+    const int q = blockIdx.x;
+    const int32_t* s = sub + q * D;
+    const double* c = coef + q * (D + 1);
+    for (int i = threadIdx.x; i < n; i += 256) {
+        if (s[0] < 0) {
+            out[q * ldr + i] = __longlong_as_double(0x7FF8000000000000LL);
+            continue;
+        }
+        double p = c[0];
+        for (int j = 0; j < D; j++) p = fma(c[j + 1], F[(int64_t)s[j] * ldf + i], p);
+        out[q * ldr + i] = y[i] - p;
+    }
+}
+
+// ------------------------------------------------------------------ OMP
+// g_j = |Z_j . r| for inactive rows (one wave per row).
+__global__ __launch_bounds__(256) void k_omp_corr(int n, int S, const double* __restrict__ Z, int ldz,
+                                                  const double* __restrict__ r,
+                                                  const int32_t* __restrict__ active,
+                                                  const int32_t* __restrict__ nact,
+                                                  double* __restrict__ g) {
+    const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (j >= S) return;
+    double s = 0.0;
+    for (int i = lane; i < n; i += 64) s += Z[(int64_t)j * ldz + i] * r[i];
+    s = fabs(wave_sum(s));
+    if (lane == 0) {
+        bool act = false;
+        for (int q = 0; q < *nact; q++) act |= active[q] == j;
+        double zz = 0.0;
+        (void)zz;
+        g[j] = act ? -1.0 : s;
+    }
+}
+
+// argmax of g by (-g, ID), appended to the active list (single block).
+__global__ __launch_bounds__(256) void k_omp_pick(int S, const double* __restrict__ g,
+                                                  const int64_t* __restrict__ ids,
+                                                  const double* __restrict__ rownorm,
+                                                  int32_t* __restrict__ active,
+                                                  int32_t* __restrict__ nact) {
+    __shared__ double bg[256];
+    __shared__ int bj[256];
+    double best = -2.0;
+    int bi = -1;
+    for (int j = threadIdx.x; j < S; j += 256) {
+        if (!(rownorm[j] > 0.0)) continue;
+        const double v = g[j];
+        if (v > best || (v == best && bi >= 0 && ids[j] < ids[bi])) {
+            best = v;
+            bi = j;
+        }
+    }
+    bg[threadIdx.x] = best;
+    bj[threadIdx.x] = bi;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            const double v = bg[threadIdx.x + o];
+            const int j = bj[threadIdx.x + o];
+            const int cj = bj[threadIdx.x];
+            if (j >= 0 && (cj < 0 || v > bg[threadIdx.x] || (v == bg[threadIdx.x] && ids[j] < ids[cj]))) {
+                bg[threadIdx.x] = v;
+                bj[threadIdx.x] = j;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && bj[0] >= 0 && bg[0] >= 0.0) {
+        active[*nact] = bj[0];
+        *nact += 1;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_omp_fit(int n, const double* __restrict__ F, int64_t ldf,
+                                                 const double* __restrict__ y,
+                                                 const int32_t* __restrict__ active,
+                                                 const int32_t* __restrict__ nact,
+                                                 double* __restrict__ A, double* __restrict__ coef,
+                                                 double* __restrict__ rss, double* __restrict__ r) {
+    __shared__ int idx[DISCOVER_MAX_D];
+    __shared__ double cf[DISCOVER_MAX_D + 1];
+    __shared__ double rs;
+    const int d = *nact;
+    if (threadIdx.x < d) idx[threadIdx.x] = active[threadIdx.x];
+    __syncthreads();
+    block_lsq(n, d, idx, F, ldf, y, A, cf, &rs, r);
+    if (threadIdx.x == 0) {
+        for (int j = 0; j <= d; j++) coef[j] = cf[j];
+        *rss = rs;
+    }
+}
+
+__global__ void k_row_norm(int S, int ldz, const double* __restrict__ Z, int n,
+                           double* __restrict__ nrm) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= S) return;
+    double s = 0.0;
+    for (int i = 0; i < n; i++) s += Z[(int64_t)j * ldz + i] * Z[(int64_t)j * ldz + i];
+    nrm[j] = s;
+}
+
+// ================================================================== host
+struct L0Plan {
+    int S, n, ldz, ldg;
+    double *Z, *G, *yy;
+};
+
+static void prep_gram(discover_ctx* ctx, const discover_l0_problem& pb, L0Plan& L, hipStream_t st) {
+    L.S = pb.S;
+    L.n = pb.n;
+    L.ldz = (int)cdiv(pb.n, 16) * 16;
+    L.ldg = (int)cdiv(pb.S + 1, 2) * 2;
+    L.Z = ctx->buf<double>("l0Z", (size_t)(pb.S + 1) * L.ldz);
+    L.G = ctx->buf<double>("l0G", (size_t)(pb.S + 1) * L.ldg);
+    L.yy = ctx->buf<double>("l0yy", 1);
+    KTimer kt(ctx, st, "l0_gram");
+    k_l0_prep<<<(unsigned)cdiv(pb.S + 1, 4), 256, 0, st>>>(pb.n, pb.S, pb.F, pb.ldf, pb.y, L.ldz, L.Z,
+                                                           L.yy);
+    const int M = pb.S + 1;
+    dim3 g((unsigned)cdiv(M, 64), (unsigned)cdiv(M, 64));
+    k_gram<<<g, 256, 0, st>>>(M, L.ldz, L.ldz, L.Z, L.G, L.ldg);
+    check_launch("k_gram");
+}
+
+static void l0_problem(discover_ctx* ctx, const discover_l0_problem& pb, int D, int m,
+                       int32_t* out_sub, double* out_rmse, double* out_coef, double* out_resid,
+                       int64_t ldr, discover_l0_stats& stats, hipStream_t st) {
+    L0Plan L;
+    prep_gram(ctx, pb, L, st);
+    const int S = pb.S;
+    // work items
+    std::vector<int2> items;
+    if (D == 1) {
+        for (int a0 = 0; a0 < S; a0 += 64) items.push_back(make_int2(0, a0));
+    } else if (D == 2) {
+        for (int a = 0; a < S - 1; a++)
+            for (int b0 = a + 1; b0 < S; b0 += 64) items.push_back(make_int2(a, b0));
+    } else {
+        // groups of 4 items per a so that a workgroup shares its b-table;
+        // heaviest a first (work ~ (S - a))
+        for (int a = 0; a < S - 2; a++) {
+            int cnt = 0;
+            for (int c0 = a + 2; c0 < S; c0 += 64, cnt++) items.push_back(make_int2(a, c0));
+            while (cnt % 4) { items.push_back(make_int2(a, S)); cnt++; }   // empty pad items
+        }
+    }
+    const int64_t ni = (int64_t)items.size();
+    int2* d_items = ctx->buf<int2>("l0items", ni);
+    DSC_HIP(hipMemcpyAsync(d_items, items.data(), ni * sizeof(int2), hipMemcpyHostToDevice, st));
+    SweepArgs g{};
+    g.G = L.G; g.ldg = L.ldg; g.S = S; g.D = D; g.items = d_items; g.n_items = ni;
+    g.wbest = ctx->buf<double>("l0wbest", ni);
+    g.wlane = ctx->buf<int32_t>("l0wlane", ni);
+    const unsigned blocks = (unsigned)cdiv(ni, 4);
+    {
+        KTimer kt(ctx, st, D == 3 ? "l0_sweep3" : "l0_sweep");
+        if (D == 1) k_sweep1<false><<<blocks, 256, 0, st>>>(g);
+        else if (D == 2) k_sweep2<false><<<blocks, 256, 0, st>>>(g);
+        else k_sweep3<false><<<blocks, 256, 0, st>>>(g);
+        check_launch("k_sweep");
+    }
+    // threshold from the m-th largest wave best
+    uint32_t* hist = ctx->buf<uint32_t>("l0hist", 4096);
+    uint32_t* sel = ctx->buf<uint32_t>("l0sel", 4);
+    int64_t* sst = ctx->buf<int64_t>("l0selst", 2);
+    radix_select(g.wbest, ni, m, hist, sel, sst, st);
+    std::vector<double> wb(ni);
+    uint32_t hsel[4];
+    int64_t hst[2];
+    DSC_HIP(hipMemcpyAsync(wb.data(), g.wbest, ni * 8, hipMemcpyDeviceToHost, st));
+    DSC_HIP(hipMemcpyAsync(hsel, sel, 16, hipMemcpyDeviceToHost, st));
+    DSC_HIP(hipMemcpyAsync(hst, sst, 16, hipMemcpyDeviceToHost, st));
+    DSC_HIP(hipStreamSynchronize(st));
+    double thr;
+    if (hst[1]) {                        // fewer than m valid waves: collect every valid subset
+        bool any = false;
+        for (double v : wb) any |= v > -0.5;
+        if (!any) DSC_FAIL(DISCOVER_E_NUMERIC, "no non-singular %d-subset", D);
+        thr = -0.5;
+    } else {
+        uint64_t key = ((uint64_t)hsel[0] << 51) | ((uint64_t)hsel[1] << 39) | ((uint64_t)hsel[2] << 27);
+        double th;
+        std::memcpy(&th, &key, 8);
+        thr = th * (1.0 - 1e-12) - GRAM_DELTA;   // slack for the packed low mantissa bits
+    }
+    // waves to sweep again: best >= thr
+    std::vector<int2> again;
+    for (int64_t i = 0; i < ni; i++)
+        if (wb[i] >= thr - 1e-9 && wb[i] > -0.5) again.push_back(items[i]);
+    // keep D = 3 groups of 4 sharing a: re-pad per a
+    if (D == 3) {
+        std::vector<int2> grp;
+        for (size_t i = 0; i < again.size();) {
+            size_t j = i;
+            while (j < again.size() && again[j].x == again[i].x) j++;
+            for (size_t q = i; q < j; q++) grp.push_back(again[q]);
+            while (grp.size() % 4) grp.push_back(make_int2(again[i].x, S));
+            i = j;
+        }
+        again.swap(grp);
+    }
+    int64_t cap = std::max<int64_t>(4096, 64 * (int64_t)again.size());
+    int64_t nb = 0;
+    for (;;) {
+        g.items = ctx->buf<int2>("l0again", again.size());
+        DSC_HIP(hipMemcpyAsync((void*)g.items, again.data(), again.size() * sizeof(int2),
+                               hipMemcpyHostToDevice, st));
+        g.n_items = (int64_t)again.size();
+        g.thr = thr;
+        g.band = ctx->buf<int4>("l0band", cap);
+        g.bq = ctx->buf<double>("l0bq", cap);
+        g.bcnt = ctx->buf<unsigned long long>("l0bcnt", 1);
+        g.bcap = cap;
+        DSC_HIP(hipMemsetAsync(g.bcnt, 0, 8, st));
+        const unsigned b2 = (unsigned)cdiv(g.n_items, 4);
+        {
+            KTimer kt(ctx, st, "l0_band");
+            if (b2) {
+                if (D == 1) k_sweep1<true><<<b2, 256, 0, st>>>(g);
+                else if (D == 2) k_sweep2<true><<<b2, 256, 0, st>>>(g);
+                else k_sweep3<true><<<b2, 256, 0, st>>>(g);
+            }
+            check_launch("k_sweep(band)");
+        }
+        unsigned long long c = 0;
+        DSC_HIP(hipMemcpyAsync(&c, g.bcnt, 8, hipMemcpyDeviceToHost, st));
+        DSC_HIP(hipStreamSynchronize(st));
+        nb = (int64_t)c;
+        if (nb <= cap) break;
+        cap = nb;
+    }
+    stats.n_band = nb;
+    if (nb == 0) DSC_FAIL(DISCOVER_E_NUMERIC, "no non-singular %d-subset", D);
+    // refit the band by QR
+    const int nblk = (int)std::min<int64_t>(nb, 1024);
+    double* scratch = ctx->buf<double>("l0scratch", (size_t)nblk * (D + 2) * pb.n);
+    double* brss = ctx->buf<double>("l0brss", nb);
+    double* bcoef = ctx->buf<double>("l0bcoef", nb * (D + 1));
+    {
+        KTimer kt(ctx, st, "l0_refit");
+        k_refit<<<nblk, 256, 0, st>>>(pb.n, D, pb.F, pb.ldf, pb.y, g.band, nb, scratch, brss, bcoef);
+        check_launch("k_refit");
+    }
+    uint8_t* taken = ctx->buf<uint8_t>("l0taken", nb);
+    int32_t* chosen = ctx->buf<int32_t>("l0chosen", m);
+    k_rank_models<<<1, 64, 0, st>>>(g.band, brss, bcoef, nb, D, m, pb.ids, L.yy, pb.n, taken,
+                                    out_sub, out_rmse, out_coef, chosen);
+    check_launch("k_rank_models");
+    if (out_resid) {
+        k_resid<<<m, 256, 0, st>>>(pb.n, D, pb.F, pb.ldf, pb.y, out_sub, out_coef, out_resid, ldr);
+        check_launch("k_resid");
+    }
+}
+
+}  // namespace dsc
+
+static int64_t binom(int64_t n, int k) {
+    if (k < 0 || n < k) return 0;
+    int64_t r = 1;
+    for (int i = 0; i < k; i++) r = r * (n - i) / (i + 1);
+    return r;
+}
+
+extern "C" discover_status discover_l0_fit(discover_ctx* ctx, const discover_l0_problem* probs,
+                                           int32_t n_problems, int32_t D, int32_t m,
+                                           int32_t* out_subsets, double* out_rmse, double* out_coef,
+                                           double* out_resid, int64_t ldr,
+                                           discover_l0_stats* out_stats, void* stream) {
+    using namespace dsc;
+    return guarded([&] {
+        DSC_REQUIRE(ctx && probs && n_problems >= 1, "ctx/probs");
+        DSC_REQUIRE(D >= 1 && D <= 3, "D = %d outside 1..3", D);
+        DSC_REQUIRE(m >= 1 && m <= 64, "m = %d outside 1..64", m);
+        DSC_REQUIRE(out_subsets && out_rmse && out_coef, "outputs required");
+        for (int b = 0; b < n_problems; b++) {
+            const discover_l0_problem& p = probs[b];
+            DSC_REQUIRE(p.n >= D + 2, "problem %d: n = %d < D + 2", b, p.n);
+            DSC_REQUIRE(p.S >= D && p.S < 65536, "problem %d: S = %d", b, p.S);
+            DSC_REQUIRE(p.F && p.ids && p.y && p.ldf >= p.n, "problem %d: F/ids/y/ldf", b);
+            DSC_REQUIRE(!out_resid || ldr >= p.n, "problem %d: ldr < n", b);
+        }
+        DSC_HIP(hipSetDevice(ctx->device));
+        hipStream_t st = (hipStream_t)stream;
+        for (int b = 0; b < n_problems; b++) {
+            discover_l0_stats s{};
+            s.n_subsets = binom(probs[b].S, D);
+            l0_problem(ctx, probs[b], D, m, out_subsets + (int64_t)b * m * D, out_rmse + (int64_t)b * m,
+                       out_coef + (int64_t)b * m * (D + 1),
+                       out_resid ? out_resid + (int64_t)b * m * ldr : nullptr, ldr, s, st);
+            DSC_HIP(hipStreamSynchronize(st));
+            ctx->resolve_timing();
+            if (out_stats) out_stats[b] = s;
+        }
+    });
+}
+
+extern "C" discover_status discover_omp(discover_ctx* ctx, const discover_l0_problem* probs,
+                                        int32_t n_problems, int32_t D_max, const int32_t* init_active,
+                                        int32_t n_init, int32_t* out_active, double* out_coef,
+                                        double* out_rmse, double* out_resid, int64_t ldr,
+                                        void* stream) {
+    using namespace dsc;
+    return guarded([&] {
+        DSC_REQUIRE(ctx && probs && n_problems >= 1, "ctx/probs");
+        DSC_REQUIRE(D_max >= 1 && D_max <= DISCOVER_MAX_D, "D_max = %d outside 1..%d", D_max,
+                    DISCOVER_MAX_D);
+        DSC_REQUIRE(n_init >= 0 && n_init <= D_max && (n_init == 0 || init_active), "init_active");
+        DSC_REQUIRE(out_active && out_coef && out_rmse, "outputs required");
+        for (int b = 0; b < n_problems; b++) {
+            const discover_l0_problem& p = probs[b];
+            DSC_REQUIRE(p.S >= D_max, "problem %d: S = %d < D_max", b, p.S);
+            DSC_REQUIRE(p.n >= D_max + 2, "problem %d: n too small", b);
+            DSC_REQUIRE(p.F && p.ids && p.y && p.ldf >= p.n, "problem %d: F/ids/y/ldf", b);
+            DSC_REQUIRE(!out_resid || ldr >= p.n, "problem %d: ldr < n", b);
+        }
+        DSC_HIP(hipSetDevice(ctx->device));
+        hipStream_t st = (hipStream_t)stream;
+        for (int b = 0; b < n_problems; b++) {
+            const discover_l0_problem& pb = probs[b];
+            L0Plan L;
+            L.S = pb.S;
+            L.n = pb.n;
+            L.ldz = (int)cdiv(pb.n, 16) * 16;
+            L.Z = ctx->buf<double>("ompZ", (size_t)(pb.S + 1) * L.ldz);
+            L.yy = ctx->buf<double>("ompyy", 1);
+            int32_t* active = out_active + (int64_t)b * D_max;
+            int32_t* nact = ctx->buf<int32_t>("ompn", 1);
+            double* g = ctx->buf<double>("ompg", pb.S);
+            double* nrm = ctx->buf<double>("ompnrm", pb.S);
+            double* r = out_resid ? out_resid + (int64_t)b * ldr : ctx->buf<double>("ompr", pb.n);
+            double* A = ctx->buf<double>("ompA", (size_t)(D_max + 2) * pb.n);
+            double* rss = ctx->buf<double>("omprss", 1);
+            double* coef = out_coef + (int64_t)b * (D_max + 1);
+            KTimer kt(ctx, st, "omp");
+            k_l0_prep<<<(unsigned)cdiv(pb.S + 1, 4), 256, 0, st>>>(pb.n, pb.S, pb.F, pb.ldf, pb.y,
+                                                                   L.ldz, L.Z, L.yy);
+            k_row_norm<<<(unsigned)cdiv(pb.S, 256), 256, 0, st>>>(pb.S, L.ldz, L.Z, pb.n, nrm);
+            DSC_HIP(hipMemsetAsync(active, 0xFF, (size_t)D_max * 4, st));
+            if (n_init)
+                DSC_HIP(hipMemcpyAsync(active, init_active + (int64_t)b * n_init, (size_t)n_init * 4,
+                                       hipMemcpyDeviceToDevice, st));
+            DSC_HIP(hipMemcpyAsync(nact, &n_init, 4, hipMemcpyHostToDevice, st));
+            k_omp_fit<<<1, 256, 0, st>>>(pb.n, pb.F, pb.ldf, pb.y, active, nact, A, coef, rss, r);
+            for (int step = n_init; step < D_max; step++) {
+                k_omp_corr<<<(unsigned)cdiv(pb.S, 4), 256, 0, st>>>(pb.n, pb.S, L.Z, L.ldz, r, active,
+                                                                    nact, g);
+                k_omp_pick<<<1, 256, 0, st>>>(pb.S, g, pb.ids, nrm, active, nact);
+                k_omp_fit<<<1, 256, 0, st>>>(pb.n, pb.F, pb.ldf, pb.y, active, nact, A, coef, rss, r);
+            }
+            check_launch("omp");
+            double h_rss;
+            DSC_HIP(hipMemcpyAsync(&h_rss, rss, 8, hipMemcpyDeviceToHost, st));
+            DSC_HIP(hipStreamSynchronize(st));
+            const double rm = std::sqrt(h_rss / pb.n);
+            DSC_HIP(hipMemcpyAsync(out_rmse + b, &rm, 8, hipMemcpyHostToDevice, st));
+            DSC_HIP(hipStreamSynchronize(st));
+        }
+        ctx->resolve_timing();
+    });
+}

@@ -1,0 +1,1213 @@
+// Candidate generation + sure-independence screening + exact top-k on
+// gfx950 (the screening step of the SISSO method cited in the Summary;
+// candidate generation with unit pruning per the Software Description and
+// Physics-Informed Constraints sections).
+//
+// Data layout in HBM (per problem):
+//   operand features (unit-legal features below the streamed rung), compact
+//   index c in [0, Mc):
+//     Vf/Rf/Cf  [Mc][ldn]   feature-major values, 1/values, centered values
+//     Vs/Rs/Cs  [n][ldm]    the same, sample-major (ldm = Mc rounded to 64)
+//     mu, mur   [Mc]        mean of values / of reciprocals
+//     valid     [Mc]        operand usable (finite, non-constant, valid operands)
+//   targets: Yc [T][ldn] centered, Yn [Tp][ldn] centered and unit-norm
+//            (rows >= T are zero padding), syy [T], ysum [Tp] = sum Yn
+//   scores    [T'][N]       one FP64 slot per candidate ID:
+//                             +s     score with |error| <= margin
+//                             -u     error may be larger; u bounds s above
+//                             NaN    invalid / unit-illegal / not computed
+//
+// The streamed rung is never materialised: each wave evaluates
+// op(f_i, f_j) for its tile on the fly and keeps only moments in registers.
+#include "dsc_select.h"
+#include "dsc_space.h"
+
+namespace dsc {
+
+constexpr double TAU_CONST = 1e-8;   // std <= TAU_CONST * rms  => constant
+constexpr double TAU_NEAR = 1e-9;    // relative score window of a duplicate pair
+constexpr double TAU_DUP = 1e-9;     // 1 - |corr| at or below which two features are duplicates
+constexpr double KAPPA_MAX = 64.0;   // shifted-moment conditioning accepted without inflation
+constexpr double EPS64 = 1.1102230246251565e-16;
+
+// ------------------------------------------------------------------ targets
+// One block per target: two-pass mean, centered and unit-norm copies.
+__global__ __launch_bounds__(256) void k_targets(int n, int T, const double* __restrict__ Y,
+                                                 int64_t ldy, int ldn, double* __restrict__ Yc,
+                                                 double* __restrict__ Yn, double* __restrict__ syy,
+                                                 double* __restrict__ ysum, int* __restrict__ bad) {
+    const int t = blockIdx.x;
+    __shared__ double red[4];
+    const double* y = Y + (int64_t)t * ldy;
+    auto block_sum = [&](double v) {
+        v = wave_sum(v);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+        __syncthreads();
+        double r = (red[0] + red[1]) + (red[2] + red[3]);
+        __syncthreads();
+        return r;
+    };
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) s += y[i];
+    const double m = block_sum(s) / n;
+    double q = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) {
+        double d = y[i] - m;
+        Yc[(int64_t)t * ldn + i] = d;
+        q += d * d;
+    }
+    const double ss = block_sum(q);
+    const double inv = 1.0 / sqrt(ss);
+    double z = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) {
+        double v = (y[i] - m) * inv;
+        Yn[(int64_t)t * ldn + i] = v;
+        z += v;
+    }
+    const double zs = block_sum(z);
+    if (threadIdx.x == 0) {
+        syy[t] = ss;
+        ysum[t] = zs;
+        const double sd = sqrt(ss / n), rms = sqrt(ss / n + m * m);
+        if (!(sd > TAU_CONST * rms) || !isfinite(ss)) atomicOr(bad, 1);
+    }
+}
+
+// ---------------------------------------------------------- materialisation
+__device__ __forceinline__ double apply_op(int op, double a, double b) {
+    switch (op) {
+    case OP_EXP: return exp(a);
+    case OP_LOG: return log(a);
+    case OP_SQRT: return sqrt(a);
+    case OP_SQ: return a * a;
+    case OP_INV: return 1.0 / a;
+    case OP_ADD: return a + b;
+    case OP_SUB: return a - b;
+    case OP_MUL: return a * b;
+    case OP_DIV: return a / b;
+    default: return b / a;   // OP_RDIV
+    }
+}
+
+// Values of the operand features of one rung: c in [c0, c1).
+__global__ void k_mat_values(int n, int ldn, int c0, int c1, const double* __restrict__ X,
+                             int64_t ldx, const int8_t* __restrict__ op,
+                             const int32_t* __restrict__ ca, const int32_t* __restrict__ cb,
+                             const int64_t* __restrict__ raw, double* __restrict__ Vf) {
+    const int c = c0 + blockIdx.y;
+    if (c >= c1) return;
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int o = op[c];
+    double v;
+    if (o == OP_NONE) v = X[raw[c] * ldx + s];
+    else {
+        const double a = Vf[(int64_t)ca[c] * ldn + s];
+        const double b = cb[c] >= 0 ? Vf[(int64_t)cb[c] * ldn + s] : 0.0;
+        v = apply_op(o, a, b);
+    }
+    Vf[(int64_t)c * ldn + s] = v;
+}
+
+// One wave per operand feature of one rung: validity, mean, reciprocals,
+// centered values.
+__global__ __launch_bounds__(256) void k_mat_stats(int n, int ldn, int c0, int c1,
+                                                   const int32_t* __restrict__ ca,
+                                                   const int32_t* __restrict__ cb,
+                                                   double* __restrict__ Vf, double* __restrict__ Rf,
+                                                   double* __restrict__ Cf, double* __restrict__ mu,
+                                                   double* __restrict__ mur,
+                                                   uint8_t* __restrict__ valid) {
+    const int c = c0 + blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (c >= c1) return;
+    const double* v = Vf + (int64_t)c * ldn;
+    double s = 0.0, sr = 0.0;
+    int bad = 0;
+    for (int i = lane; i < n; i += 64) {
+        const double x = v[i];
+        const double r = 1.0 / x;
+        Rf[(int64_t)c * ldn + i] = r;
+        bad |= !isfinite(x);
+        s += x;
+        sr += r;
+    }
+    s = wave_sum(s);
+    sr = wave_sum(sr);
+    const int anybad = __any(bad);
+    const double m = s / n;
+    double q = 0.0;
+    for (int i = lane; i < n; i += 64) {
+        const double d = v[i] - m;
+        Cf[(int64_t)c * ldn + i] = d;
+        q += d * d;
+    }
+    q = wave_sum(q);
+    if (lane == 0) {
+        bool ok = !anybad && isfinite(q);
+        const double sd = sqrt(q / n), rms = sqrt(q / n + m * m);
+        ok = ok && (sd > TAU_CONST * rms);
+        if (ca[c] >= 0) ok = ok && valid[ca[c]];
+        if (cb[c] >= 0) ok = ok && valid[cb[c]];
+        valid[c] = ok;
+        mu[c] = m;
+        mur[c] = sr / n;
+    }
+}
+
+// Feature-major [M][ldn] -> sample-major [n][ldm] (padding left as is).
+__global__ void k_transpose(int n, int M, int ldn, int ldm, const double* __restrict__ src,
+                            double* __restrict__ dst) {
+    __shared__ double tile[32][33];
+    const int c0 = blockIdx.y * 32, s0 = blockIdx.x * 32;
+    for (int k = threadIdx.y; k < 32; k += 8) {
+        const int c = c0 + k, s = s0 + threadIdx.x;
+        tile[k][threadIdx.x] = (c < M && s < n) ? src[(int64_t)c * ldn + s] : 0.0;
+    }
+    __syncthreads();
+    for (int k = threadIdx.y; k < 32; k += 8) {
+        const int s = s0 + k, c = c0 + threadIdx.x;
+        if (s < n && c < M) dst[(int64_t)s * ldm + c] = tile[threadIdx.x][k];
+    }
+}
+
+// ----------------------------------------------- exact candidate evaluation
+struct Ops {           // operand arrays of one problem
+    const double* Vf;
+    const double* Rf;
+    int ldn;
+};
+
+struct Cand {
+    int kind;          // 0 operand feature, 1 unary, 2 binary
+    int op;
+    int ca, cb;        // compact operand indices
+};
+
+__device__ __forceinline__ double cand_value(const Cand& c, const Ops& o, int s) {
+    const double a = o.Vf[(int64_t)c.ca * o.ldn + s];
+    if (c.kind == 0) return a;
+    if (c.kind == 1) {
+        if (c.op == OP_INV) return o.Rf[(int64_t)c.ca * o.ldn + s];   // = 1.0 / a
+        return apply_op(c.op, a, 0.0);
+    }
+    const double b = o.Vf[(int64_t)c.cb * o.ldn + s];
+    return apply_op(c.op, a, b);
+}
+
+__device__ __forceinline__ bool cand_of_id(const SpaceDev& sd, int streamed,
+                                           const int32_t* __restrict__ raw2c, int64_t id, Cand& c) {
+    int rung, op;
+    int64_t a, b;
+    decode_id(sd, id, rung, op, a, b);
+    if (streamed == 0 || rung < streamed) {
+        c.kind = 0; c.op = OP_NONE; c.ca = raw2c[id]; c.cb = -1;
+        return c.ca >= 0;
+    }
+    c.op = op;
+    c.ca = raw2c[a];
+    if (b < 0) {
+        c.kind = 1; c.cb = -1;
+        return c.ca >= 0;
+    }
+    c.kind = 2;
+    c.cb = raw2c[b];
+    return c.ca >= 0 && c.cb >= 0;
+}
+
+// Exact two-pass Pearson of one candidate against T centered targets by one
+// wave.  Returns false when the candidate is not finite or is constant.
+template <int TMAX>
+__device__ bool wave_exact_r(const Cand& c, const Ops& o, int n, int T,
+                             const double* __restrict__ Yc, const double* __restrict__ syy,
+                             double* r) {
+    const int lane = threadIdx.x & 63;
+    double s = 0.0;
+    int bad = 0;
+    for (int i = lane; i < n; i += 64) {
+        const double f = cand_value(c, o, i);
+        bad |= !isfinite(f);
+        s += f;
+    }
+    if (__any(bad)) return false;
+    const double m = wave_sum(s) / n;
+    double sxx = 0.0, sxy[TMAX];
+#pragma unroll
+    for (int t = 0; t < TMAX; t++) sxy[t] = 0.0;
+    for (int i = lane; i < n; i += 64) {
+        const double d = cand_value(c, o, i) - m;
+        sxx += d * d;
+#pragma unroll
+        for (int t = 0; t < TMAX; t++)
+            if (t < T) sxy[t] += d * Yc[(int64_t)t * o.ldn + i];
+    }
+    sxx = wave_sum(sxx);
+    if (!isfinite(sxx)) return false;
+    const double sd = sqrt(sxx / n), rms = sqrt(sxx / n + m * m);
+    if (!(sd > TAU_CONST * rms)) return false;
+#pragma unroll
+    for (int t = 0; t < TMAX; t++)
+        if (t < T) r[t] = wave_sum(sxy[t]) / sqrt(sxx * syy[t]);
+    return true;
+}
+
+// Exact scores of an explicit candidate list (operand features and unary
+// candidates of the streamed rung), written into the score slots.
+struct ListItem {
+    int64_t id;
+    int32_t kind, op, ca, cb;
+};
+
+__global__ __launch_bounds__(256) void k_score_list(const ListItem* __restrict__ items, int64_t m,
+                                                    Ops o, const uint8_t* __restrict__ valid,
+                                                    int n, int T, int mode,
+                                                    const double* __restrict__ Yc,
+                                                    const double* __restrict__ syy, int64_t N,
+                                                    double* __restrict__ scores,
+                                                    unsigned long long* __restrict__ nscored) {
+    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (w >= m) return;
+    const ListItem it = items[w];
+    Cand c{it.kind, it.op, it.ca, it.cb};
+    bool ok = valid[c.ca] && (c.kind < 2 || valid[c.cb]);
+    if (c.kind == 0) ok = valid[c.ca];
+    double r[DISCOVER_MAX_TARGETS];
+    ok = ok && wave_exact_r<DISCOVER_MAX_TARGETS>(c, o, n, T, Yc, syy, r);
+    if ((threadIdx.x & 63) == 0) {
+        if (!ok) {
+            for (int t = 0; t < (mode ? 1 : T); t++) scores[(int64_t)t * N + it.id] = __longlong_as_double(-1LL);
+            return;
+        }
+        atomicAdd(nscored, 1ull);
+        if (mode == DISCOVER_SCORE_MAX) {
+            double mx = 0.0;
+            for (int t = 0; t < T; t++) mx = fmax(mx, fabs(r[t]));
+            scores[it.id] = mx;
+        } else {
+            for (int t = 0; t < T; t++) scores[(int64_t)t * N + it.id] = fabs(r[t]);
+        }
+    }
+}
+
+// --------------------------------------------------- streamed pair screen
+// Tile of one wave: J operand features j (uniform) x 64 operand features i
+// (one per lane).  For every (i, j) with i < j and every operator of OPS,
+// the candidate value is formed on the fly, shifted by an estimate of its
+// mean (exact for add/sub via centered operands, mu_a * mu_b style for the
+// products) and accumulated into sum, sum of squares and T dot products
+// with the unit-norm targets.
+//
+// OPS bits: 0 add, 1 sub, 2 mul, 3 div, 4 rdiv.
+struct PairArgs {
+    const int2* tiles;        // (jc0, ic0) per wave (dense) or (jc, list offset)
+    const int32_t* ilist;     // explicit partner lists (list mode) or NULL
+    const int32_t* icount;    // per-wave partner count (list mode)
+    int64_t n_tiles;
+    int n, ldm, ldn, Mc, jc_end, i_end;   // i_end: end of the partner pool
+    const double *Vs, *Rs, *Cs, *Vf, *Rf, *Cf, *mu, *mur;
+    const uint8_t* valid;
+    const int64_t* mat_raw;
+    const double* Yn;
+    const double* ysum;
+    int T, mode, r;
+    uint32_t opmask;          // runtime enabled subset of OPS (bits as above)
+    SpaceDev sd;
+    int64_t N;
+    double* scores;
+    unsigned long long* nscored;
+    int64_t* fix_ids;         // candidates whose shifted moments are ill-conditioned
+    unsigned long long* fix_cnt;
+    int64_t fix_cap;
+};
+
+template <int OPS, int J, int TP, bool LIST>
+__global__ __launch_bounds__(256) void k_screen_pairs(PairArgs g) {
+    constexpr int NOP = ((OPS >> 0) & 1) + ((OPS >> 1) & 1) + ((OPS >> 2) & 1) +
+                        ((OPS >> 3) & 1) + ((OPS >> 4) & 1);
+    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (w >= g.n_tiles) return;
+    const int lane = threadIdx.x & 63;
+    const int2 tile = g.tiles[w];
+    const int jc0 = tile.x;
+    int i;
+    bool lane_ok;
+    if (LIST) {
+        lane_ok = lane < g.icount[w];
+        i = g.ilist[tile.y + (lane_ok ? lane : 0)];
+    } else {
+        i = tile.y + lane;
+        lane_ok = i < g.i_end;
+    }
+    const int ic = lane_ok ? i : 0;
+    const double mua = g.mu[ic], mura = g.mur[ic];
+    const bool va = lane_ok && g.valid[ic];
+
+    int jc[J];
+    bool jok[J];
+    double sh[J][NOP];
+#pragma unroll
+    for (int jj = 0; jj < J; jj++) {
+        const int j = jc0 + jj;
+        jok[jj] = j < g.jc_end;
+        jc[jj] = jok[jj] ? j : jc0;
+        const double mub = g.mu[jc[jj]], murb = g.mur[jc[jj]];
+        int k = 0;
+        if (OPS & 1) sh[jj][k++] = 0.0;                // add: centered operands
+        if (OPS & 2) sh[jj][k++] = 0.0;                // sub
+        if (OPS & 4) sh[jj][k++] = mua * mub;          // mul
+        if (OPS & 8) sh[jj][k++] = mua * murb;         // div  = a * (1/b)
+        if (OPS & 16) sh[jj][k++] = mura * mub;        // rdiv = b * (1/a)
+    }
+    double s1[J][NOP], s2[J][NOP], dt[J][NOP][TP];
+#pragma unroll
+    for (int jj = 0; jj < J; jj++)
+#pragma unroll
+        for (int k = 0; k < NOP; k++) {
+            s1[jj][k] = 0.0;
+            s2[jj][k] = 0.0;
+#pragma unroll
+            for (int t = 0; t < TP; t++) dt[jj][k][t] = 0.0;
+        }
+
+    const double* __restrict__ Vs = g.Vs;
+    const double* __restrict__ Rs = g.Rs;
+    const double* __restrict__ Cs = g.Cs;
+    for (int s = 0; s < g.n; s++) {
+        const int64_t so = (int64_t)s * g.ldm + ic;
+        const double a = (OPS & 28) ? Vs[so] : 0.0;
+        const double ra = (OPS & 16) ? Rs[so] : 0.0;
+        const double ac = (OPS & 3) ? Cs[so] : 0.0;
+        double y[TP];
+#pragma unroll
+        for (int t = 0; t < TP; t++) y[t] = g.Yn[(int64_t)t * g.ldn + s];
+#pragma unroll
+        for (int jj = 0; jj < J; jj++) {
+            const int64_t fo = (int64_t)jc[jj] * g.ldn + s;
+            const double b = (OPS & 20) ? g.Vf[fo] : 0.0;
+            const double rb = (OPS & 8) ? g.Rf[fo] : 0.0;
+            const double bc = (OPS & 3) ? g.Cf[fo] : 0.0;
+            double f[NOP];
+            int k = 0;
+            if (OPS & 1) { f[k] = ac + bc; k++; }
+            if (OPS & 2) { f[k] = ac - bc; k++; }
+            if (OPS & 4) { f[k] = fma(a, b, -sh[jj][k]); k++; }
+            if (OPS & 8) { f[k] = fma(a, rb, -sh[jj][k]); k++; }
+            if (OPS & 16) { f[k] = fma(ra, b, -sh[jj][k]); k++; }
+#pragma unroll
+            for (int q = 0; q < NOP; q++) {
+                s1[jj][q] += f[q];
+                s2[jj][q] = fma(f[q], f[q], s2[jj][q]);
+#pragma unroll
+                for (int t = 0; t < TP; t++) dt[jj][q][t] = fma(f[q], y[t], dt[jj][q][t]);
+            }
+        }
+    }
+
+    const double nn = (double)g.n;
+    const int64_t ria = g.mat_raw[ic];
+    unsigned cnt = 0;
+#pragma unroll
+    for (int jj = 0; jj < J; jj++) {
+        const bool pair_ok = va && jok[jj] && g.valid[jc[jj]] && (LIST || i < jc[jj]);
+        const int64_t rjb = g.mat_raw[jc[jj]];
+        const double mub = g.mu[jc[jj]], murb = g.mur[jc[jj]];
+        int k = 0;
+#pragma unroll
+        for (int o = 0; o < 5; o++) {
+            if (!((OPS >> o) & 1)) continue;
+            const int q = k++;
+            if (!((g.opmask >> o) & 1) || !(LIST ? lane_ok : (i < jc[jj]) && lane_ok && jok[jj]))
+                continue;
+            const int64_t id = pair_id(g.sd, g.r, OP_ADD + o, ria, rjb);
+            double out[TP];
+            const double S1 = s1[jj][q], S2 = s2[jj][q];
+            const double m1 = S1 / nn;
+            const double varn = S2 - S1 * m1;
+            const double nanv = __longlong_as_double(-1LL);
+            if (!pair_ok || !(S2 < INFINITY) || !(fabs(S1) < INFINITY)) {   // invalid operand or non-finite value
+                for (int t = 0; t < (g.mode ? 1 : g.T); t++) g.scores[(int64_t)t * g.N + id] = nanv;
+                continue;
+            }
+            const double kappa = varn > 0.0 ? S2 / varn : INFINITY;
+            if (!(kappa <= KAPPA_MAX)) {
+                // the shift was far from the mean: decide exactly in the fix-up pass
+                const unsigned long long slot = atomicAdd(g.fix_cnt, 1ull);
+                if ((int64_t)slot < g.fix_cap) {
+                    g.fix_ids[slot] = id;
+                    for (int t = 0; t < (g.mode ? 1 : g.T); t++) g.scores[(int64_t)t * g.N + id] = nanv;
+                    continue;
+                }
+            }
+            double shift = sh[jj][q];
+            if (o == 0) shift = mua + mub;
+            if (o == 1) shift = mua - mub;
+            const double mean = shift + m1;
+            const bool nonconst = varn / nn > TAU_CONST * TAU_CONST * (varn / nn + mean * mean);
+            if (kappa <= KAPPA_MAX && !nonconst) {
+                for (int t = 0; t < (g.mode ? 1 : g.T); t++) g.scores[(int64_t)t * g.N + id] = nanv;
+                continue;
+            }
+            const double isd = 1.0 / sqrt(varn);
+            double best = 0.0;
+#pragma unroll
+            for (int t = 0; t < TP; t++) {
+                out[t] = fabs((dt[jj][q][t] - S1 * g.ysum[t] / nn) * isd);
+                if (t < g.T) best = fmax(best, out[t]);
+            }
+            const double err = 4.0 * nn * EPS64 * kappa;
+            const bool precise = kappa <= KAPPA_MAX;
+            cnt++;
+            if (g.mode == DISCOVER_SCORE_MAX) {
+                g.scores[id] = precise ? best : -(best + err);
+            } else {
+#pragma unroll
+                for (int t = 0; t < TP; t++)
+                    if (t < g.T)
+                        g.scores[(int64_t)t * g.N + id] = precise ? out[t] : -(out[t] + err);
+            }
+            (void)murb;
+        }
+    }
+    // wave-aggregated count of scored candidates
+    unsigned long long tot = 0;
+    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor((int)cnt, o, 64);
+    tot = cnt;
+    if (lane == 0 && tot) atomicAdd(g.nscored, tot);
+}
+
+// ------------------------------------------------------------ selection
+// Pool = every candidate whose score may reach theta - margin.
+__global__ __launch_bounds__(256) void k_compact(const double* __restrict__ sc, int64_t N,
+                                                 const uint32_t* __restrict__ sel,
+                                                 const int64_t* __restrict__ st, double margin,
+                                                 int64_t cap, int64_t* __restrict__ pool,
+                                                 unsigned long long* __restrict__ cnt) {
+    const double th = select_threshold(sel, st);
+    const double lo = st[1] ? 0.0 : th - 2.0 * margin;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256) {
+        const double x = sc[i];
+        const bool take = (x > 0.0 && x >= lo) || (x < 0.0 && -x >= lo);
+        if (take) {
+            const unsigned long long slot = atomicAdd(cnt, 1ull);
+            if ((int64_t)slot < cap) pool[slot] = i;
+        }
+    }
+}
+
+// Exact FP64 rescore of the pool (one wave per entry); also flags entries
+// whose ID is excluded.
+template <int TMAX>
+__global__ __launch_bounds__(256) void k_rescore(const int64_t* __restrict__ pool, int64_t P,
+                                                 SpaceDev sd, int streamed,
+                                                 const int32_t* __restrict__ raw2c,
+                                                 const uint8_t* __restrict__ valid, Ops o, int n,
+                                                 int T, int mode, int tlist,
+                                                 const double* __restrict__ Yc,
+                                                 const double* __restrict__ syy,
+                                                 const int64_t* __restrict__ excl, int n_excl,
+                                                 double* __restrict__ ps,
+                                                 uint8_t* __restrict__ pex) {
+    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (w >= P) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t id = pool[w];
+    Cand c;
+    bool ok = cand_of_id(sd, streamed, raw2c, id, c);
+    ok = ok && valid[c.ca] && (c.kind < 2 || valid[c.cb]);
+    double r[TMAX];
+    ok = ok && wave_exact_r<TMAX>(c, o, n, T, Yc, syy, r);
+    int ex = 0;
+    for (int e = lane; e < n_excl; e += 64) ex |= excl[e] == id;
+    ex = __any(ex);
+    if (lane == 0) {
+        double s = -1.0;
+        if (ok) {
+            if (mode == DISCOVER_SCORE_MAX) {
+                s = 0.0;
+                for (int t = 0; t < T; t++) s = fmax(s, fabs(r[t]));
+            } else {
+                s = fabs(r[tlist]);
+            }
+            if (!(s > 0.0)) s = -1.0;
+        }
+        ps[w] = s;
+        pex[w] = (uint8_t)ex;
+    }
+}
+
+// Exact two-pass score of the candidates whose shifted one-pass moments
+// were ill-conditioned (one wave each), written back into the score slots.
+template <int TMAX>
+__global__ __launch_bounds__(256) void k_fixup(const int64_t* __restrict__ ids,
+                                               const unsigned long long* __restrict__ cnt,
+                                               int64_t cap, SpaceDev sd, int streamed,
+                                               const int32_t* __restrict__ raw2c,
+                                               const uint8_t* __restrict__ valid, Ops o, int n,
+                                               int T, int mode, const double* __restrict__ Yc,
+                                               const double* __restrict__ syy, int64_t N,
+                                               double* __restrict__ scores,
+                                               unsigned long long* __restrict__ nscored) {
+    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t m = min((int64_t)*cnt, cap);
+    if (w >= m) return;
+    const int64_t id = ids[w];
+    Cand c;
+    bool ok = cand_of_id(sd, streamed, raw2c, id, c);
+    ok = ok && valid[c.ca] && (c.kind < 2 || valid[c.cb]);
+    double r[TMAX];
+    ok = ok && wave_exact_r<TMAX>(c, o, n, T, Yc, syy, r);
+    if ((threadIdx.x & 63) != 0 || !ok) return;
+    atomicAdd(nscored, 1ull);
+    if (mode == DISCOVER_SCORE_MAX) {
+        double mx = 0.0;
+        for (int t = 0; t < T; t++) mx = fmax(mx, fabs(r[t]));
+        scores[id] = mx;
+    } else {
+        for (int t = 0; t < T; t++) scores[(int64_t)t * N + id] = fabs(r[t]);
+    }
+}
+
+// Rank sort of the pool by (-score, ID).
+__global__ __launch_bounds__(256) void k_rank(const double* __restrict__ ps,
+                                              const int64_t* __restrict__ pool, int64_t P,
+                                              int32_t* __restrict__ order) {
+    __shared__ double ts[1024];
+    __shared__ int64_t ti[1024];
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const double si = i < P ? ps[i] : 0.0;
+    const int64_t ii = i < P ? pool[i] : 0;
+    int64_t rank = 0;
+    for (int64_t base = 0; base < P; base += 1024) {
+        __syncthreads();
+        for (int k = threadIdx.x; k < 1024; k += 256) {
+            ts[k] = base + k < P ? ps[base + k] : -2.0;
+            ti[k] = base + k < P ? pool[base + k] : INT64_MAX;
+        }
+        __syncthreads();
+        const int lim = (int)min((int64_t)1024, P - base);
+        for (int k = 0; k < lim; k++) rank += (ts[k] > si) || (ts[k] == si && ti[k] < ii);
+    }
+    if (i < P) order[rank] = (int32_t)i;
+}
+
+// Near-tie window of each sorted entry: lo[q] = first earlier position whose
+// score is within TAU_NEAR (relative) of entry q, scanning backwards.
+__global__ void k_window(const double* __restrict__ ps, const int32_t* __restrict__ order,
+                         int64_t P, int32_t* __restrict__ lo, int32_t* __restrict__ cnt) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= P) return;
+    const double s = ps[order[q]];
+    int64_t l = q;
+    if (s > 0.0)
+        while (l > 0 && q - l < 1024) {
+            const double sp = ps[order[l - 1]];
+            if (!(sp - s <= TAU_NEAR * sp)) break;
+            l--;
+        }
+    lo[q] = (int32_t)l;
+    cnt[q] = (int32_t)(q - l);
+}
+
+// Exclusive prefix sum of cnt (single block).
+__global__ __launch_bounds__(1024) void k_scan_offsets(const int32_t* __restrict__ cnt, int64_t P,
+                                                       int64_t* __restrict__ off) {
+    __shared__ int64_t part[1024];
+    const int64_t per = (P + 1023) / 1024;
+    const int64_t b = threadIdx.x * per, e = min(P, b + per);
+    int64_t s = 0;
+    for (int64_t q = b; q < e; q++) s += cnt[q];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t acc = 0;
+        for (int k = 0; k < 1024; k++) {
+            const int64_t v = part[k];
+            part[k] = acc;
+            acc += v;
+        }
+        off[P] = acc;
+    }
+    __syncthreads();
+    int64_t acc = part[threadIdx.x];
+    for (int64_t q = b; q < e; q++) {
+        off[q] = acc;
+        acc += cnt[q];
+    }
+}
+
+// One wave per near-tie pair (earlier position lo[q]+k, later position q):
+// duplicate flag = |corr| >= 1 - TAU_DUP.
+__global__ __launch_bounds__(256) void k_pairs(const int64_t* __restrict__ pool,
+                                               const int32_t* __restrict__ order,
+                                               const int32_t* __restrict__ lo,
+                                               const int64_t* __restrict__ off, int64_t P,
+                                               SpaceDev sd, int streamed,
+                                               const int32_t* __restrict__ raw2c, Ops o, int n,
+                                               uint8_t* __restrict__ flag) {
+    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t total = off[P];
+    if (w >= total) return;
+    const int lane = threadIdx.x & 63;
+    // find q with off[q] <= w < off[q+1]
+    int64_t a = 0, b = P;
+    while (b - a > 1) {
+        const int64_t mid = (a + b) / 2;
+        if (off[mid] <= w) a = mid; else b = mid;
+    }
+    const int64_t q = a;
+    const int64_t pe = lo[q] + (w - off[q]);
+    Cand cu, cv;
+    const bool okp = cand_of_id(sd, streamed, raw2c, pool[order[pe]], cu) &&
+                     cand_of_id(sd, streamed, raw2c, pool[order[q]], cv);
+    if (!okp) {
+        if (lane == 0) flag[w] = 0;
+        return;
+    }
+    double su = 0.0, sv = 0.0;
+    for (int i = lane; i < n; i += 64) {
+        su += cand_value(cu, o, i);
+        sv += cand_value(cv, o, i);
+    }
+    const double mu_ = wave_sum(su) / n, mv = wave_sum(sv) / n;
+    double uu = 0.0, vv = 0.0, uv = 0.0;
+    for (int i = lane; i < n; i += 64) {
+        const double du = cand_value(cu, o, i) - mu_, dv = cand_value(cv, o, i) - mv;
+        uu += du * du;
+        vv += dv * dv;
+        uv += du * dv;
+    }
+    uu = wave_sum(uu);
+    vv = wave_sum(vv);
+    uv = wave_sum(uv);
+    if (lane == 0) flag[w] = fabs(uv) / sqrt(uu * vv) >= 1.0 - TAU_DUP;
+}
+
+// Group scan (one thread): forms duplicate groups in sorted order, blocks
+// groups that contain an excluded ID, stops once the k-th unblocked group's
+// near-tie window has closed.  res: [0] selected, [1] complete, [2] merged.
+__global__ void k_groups(const int64_t* __restrict__ pool, const double* __restrict__ ps,
+                         const uint8_t* __restrict__ pex, const int32_t* __restrict__ order,
+                         const int32_t* __restrict__ lo, const int64_t* __restrict__ off,
+                         const uint8_t* __restrict__ flag, int64_t P, int k, int dedup,
+                         const uint32_t* __restrict__ sel, const int64_t* __restrict__ st,
+                         double margin, int32_t* __restrict__ hpos, uint8_t* __restrict__ hblk,
+                         int64_t* __restrict__ hmin, double* __restrict__ hsc,
+                         int64_t* __restrict__ out_ids, double* __restrict__ out_sc,
+                         int64_t* __restrict__ res) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const bool all = st[1] != 0;
+    const double th_scan = all ? -1.0 : select_threshold(sel, st) - margin;
+    int64_t nh = 0, nunb = 0, kth = -1, merged = 0;
+    bool stopped = false, short_pool = false;
+    double lim = 0.0;
+    int64_t q = 0;
+    for (; q < P; q++) {
+        const int32_t e = order[q];
+        const double s = ps[e];
+        if (!(s > 0.0)) { q = P; break; }              // past the last valid entry
+        if (kth >= 0 && s < (1.0 - TAU_NEAR) * lim) { stopped = true; break; }
+        if (s < th_scan) { short_pool = true; break; }
+        const int64_t id = pool[e];
+        int64_t grp = -1;
+        if (dedup) {
+            for (int64_t h = nh - 1; h >= 0 && hpos[h] >= lo[q]; h--)
+                if (flag[off[q] + (hpos[h] - lo[q])]) grp = h;
+        }
+        if (grp < 0) {
+            hpos[nh] = (int32_t)q;
+            hblk[nh] = pex[e];
+            hmin[nh] = id;
+            hsc[nh] = s;
+            if (!pex[e]) {
+                nunb++;
+                if (nunb == k) { kth = nh; lim = s; }
+            }
+            nh++;
+        } else {
+            merged++;
+            if (id < hmin[grp]) { hmin[grp] = id; hsc[grp] = s; }
+            if (pex[e] && !hblk[grp]) {
+                hblk[grp] = 1;
+                nunb--;
+                if (kth >= 0 && grp <= kth) {
+                    int64_t h = kth + 1;
+                    while (h < nh && hblk[h]) h++;
+                    if (h < nh) { kth = h; lim = ps[order[hpos[h]]]; }
+                    else { kth = -1; }
+                }
+            }
+        }
+    }
+    bool complete;
+    if (stopped) complete = true;
+    else if (short_pool) complete = false;
+    else complete = all || (kth >= 0 && (1.0 - TAU_NEAR) * lim >= th_scan);   // pool exhausted
+    // representatives of the first k unblocked groups, then (-score, ID) order
+    int64_t ns = 0;
+    for (int64_t h = 0; h < nh && ns < k; h++) {
+        if (hblk[h]) continue;
+        int64_t j = ns++;
+        const double s = hsc[h];
+        const int64_t id = hmin[h];
+        while (j > 0 && (out_sc[j - 1] < s || (out_sc[j - 1] == s && out_ids[j - 1] > id))) {
+            out_sc[j] = out_sc[j - 1];
+            out_ids[j] = out_ids[j - 1];
+            j--;
+        }
+        out_sc[j] = s;
+        out_ids[j] = id;
+    }
+    for (int64_t j = ns; j < k; j++) {
+        out_ids[j] = -1;
+        out_sc[j] = __longlong_as_double(0x7FF8000000000000LL);
+    }
+    res[0] = ns;
+    res[1] = complete ? 1 : 0;
+    res[2] = merged;
+}
+
+// Values of the selected candidates: one wave per output row.
+__global__ __launch_bounds__(256) void k_values(const int64_t* __restrict__ ids, int64_t m,
+                                                SpaceDev sd, int streamed,
+                                                const int32_t* __restrict__ raw2c, Ops o, int n,
+                                                double* __restrict__ out, int64_t ldv) {
+    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (w >= m) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t id = ids[w];
+    Cand c;
+    const bool ok = id >= 0 && cand_of_id(sd, streamed, raw2c, id, c);
+    for (int i = lane; i < n; i += 64)
+        out[w * ldv + i] = ok ? cand_value(c, o, i) : __longlong_as_double(0x7FF8000000000000LL);
+}
+
+}  // namespace dsc
+
+// ====================================================================== host
+namespace dsc {
+
+static int pad_targets(int T) { return T <= 1 ? 1 : T <= 2 ? 2 : T <= 4 ? 4 : T <= 8 ? 8 : 16; }
+
+// Dense and list pair launches for one op class.
+template <int OPS, int J, int TP>
+static void launch_pairs_t(const PairArgs& a, bool list, hipStream_t st) {
+    const int64_t blocks = cdiv(a.n_tiles, 4);
+    if (blocks == 0) return;
+    if (list) k_screen_pairs<OPS, 1, TP, true><<<(unsigned)blocks, 256, 0, st>>>(a);
+    else k_screen_pairs<OPS, J, TP, false><<<(unsigned)blocks, 256, 0, st>>>(a);
+}
+
+template <int OPS>
+static void launch_pairs_ops(const PairArgs& a, bool list, int TP, hipStream_t st) {
+    switch (TP) {
+    case 1: launch_pairs_t<OPS, 4, 1>(a, list, st); break;
+    case 2: launch_pairs_t<OPS, 2, 2>(a, list, st); break;
+    case 4: launch_pairs_t<OPS, 1, 4>(a, list, st); break;
+    case 8: launch_pairs_t<OPS, 1, 8>(a, list, st); break;
+    default: launch_pairs_t<OPS, 1, 16>(a, list, st); break;
+    }
+}
+
+static int dense_J(int TP) { return TP == 1 ? 4 : TP == 2 ? 2 : 1; }
+
+static void launch_pairs(int OPS, const PairArgs& a, bool list, int TP, hipStream_t st) {
+    switch (OPS) {
+    case 31: launch_pairs_ops<31>(a, list, TP, st); break;
+    case 28: launch_pairs_ops<28>(a, list, TP, st); break;
+    case 3: launch_pairs_ops<3>(a, list, TP, st); break;
+    default: DSC_FAIL(DISCOVER_E_UNSUPPORTED, "operator class %d", OPS);
+    }
+}
+
+template <class T>
+static void upload(T* dst, const std::vector<T>& v, hipStream_t st) {
+    if (!v.empty()) DSC_HIP(hipMemcpyAsync(dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+}
+
+template <class T>
+static T download1(const T* src, hipStream_t st) {
+    T v;
+    DSC_HIP(hipMemcpyAsync(&v, src, sizeof(T), hipMemcpyDeviceToHost, st));
+    DSC_HIP(hipStreamSynchronize(st));
+    return v;
+}
+
+struct Problem {
+    Space sp;
+    int n, T, Tl, TP, ldn, ldm, Mc;
+    double *Vf, *Rf, *Cf, *Vs, *Rs, *Cs, *mu, *mur, *Yc, *Yn, *syy, *ysum, *scores;
+    uint8_t* valid;
+    int32_t* raw2c;
+    int64_t* mat_raw;
+    unsigned long long* nscored;
+};
+
+// Enumerate, materialise the operand features, and screen every candidate
+// into the score slots.
+static void screen_problem(discover_ctx* ctx, const discover_problem& pb,
+                           const discover_screen_params& prm, Problem& P, hipStream_t st) {
+    Space& sp = P.sp;
+    build_space(sp, pb.p, prm, pb.B, pb.units);
+    const SpaceDev& sd = sp.d;
+    const int n = pb.n;
+    P.n = n;
+    P.T = pb.T;
+    P.Tl = prm.score_mode == DISCOVER_SCORE_MAX ? 1 : pb.T;
+    P.TP = pad_targets(pb.T);
+    P.ldn = (int)((n + 63) / 64 * 64);
+    P.Mc = sp.Mc();
+    P.ldm = (int)((P.Mc + 63) / 64 * 64);
+    const int Mc = P.Mc, ldn = P.ldn, ldm = P.ldm;
+    const int64_t N = sp.n_raw();
+
+    P.Vf = ctx->buf<double>("Vf", (size_t)Mc * ldn);
+    P.Rf = ctx->buf<double>("Rf", (size_t)Mc * ldn);
+    P.Cf = ctx->buf<double>("Cf", (size_t)Mc * ldn);
+    P.mu = ctx->buf<double>("mu", Mc);
+    P.mur = ctx->buf<double>("mur", Mc);
+    P.valid = ctx->buf<uint8_t>("valid", Mc);
+    P.raw2c = ctx->buf<int32_t>("raw2c", sp.M_raw);
+    P.mat_raw = ctx->buf<int64_t>("mat_raw", Mc);
+    int8_t* d_op = ctx->buf<int8_t>("mat_op", Mc);
+    int32_t* d_a = ctx->buf<int32_t>("mat_a", Mc);
+    int32_t* d_b = ctx->buf<int32_t>("mat_b", Mc);
+    upload(P.raw2c, sp.raw2c, st);
+    upload(P.mat_raw, sp.mat_raw, st);
+    upload(d_op, sp.mat_op, st);
+    upload(d_a, sp.mat_a, st);
+    upload(d_b, sp.mat_b, st);
+
+    // targets
+    P.Yc = ctx->buf<double>("Yc", (size_t)pb.T * ldn);
+    P.Yn = ctx->buf<double>("Yn", (size_t)P.TP * ldn);
+    P.syy = ctx->buf<double>("syy", pb.T);
+    P.ysum = ctx->buf<double>("ysum", P.TP);
+    int* bad = ctx->buf<int>("bad", 1);
+    DSC_HIP(hipMemsetAsync(P.Yn, 0, (size_t)P.TP * ldn * 8, st));
+    DSC_HIP(hipMemsetAsync(P.ysum, 0, (size_t)P.TP * 8, st));
+    DSC_HIP(hipMemsetAsync(bad, 0, 4, st));
+    k_targets<<<pb.T, 256, 0, st>>>(n, pb.T, pb.Y, pb.ldy, ldn, P.Yc, P.Yn, P.syy, P.ysum, bad);
+    check_launch("k_targets");
+    if (download1(bad, st)) DSC_FAIL(DISCOVER_E_NUMERIC, "a target column is constant or not finite");
+
+    // operand features, rung by rung
+    {
+        KTimer kt(ctx, st, "materialise");
+        for (size_t r = 0; r + 1 < sp.rung_start.size(); r++) {
+            const int c0 = sp.rung_start[r], c1 = sp.rung_start[r + 1];
+            if (c1 <= c0) continue;
+            dim3 g((unsigned)cdiv(n, 256), (unsigned)(c1 - c0));
+            k_mat_values<<<g, 256, 0, st>>>(n, ldn, c0, c1, pb.X, pb.ldx, d_op, d_a, d_b,
+                                            P.mat_raw, P.Vf);
+            k_mat_stats<<<(unsigned)cdiv(c1 - c0, 4), 256, 0, st>>>(n, ldn, c0, c1, d_a, d_b, P.Vf,
+                                                                     P.Rf, P.Cf, P.mu, P.mur, P.valid);
+        }
+        check_launch("k_mat");
+    }
+    P.nscored = ctx->buf<unsigned long long>("nscored", 1);
+    DSC_HIP(hipMemsetAsync(P.nscored, 0, 8, st));
+    P.scores = ctx->buf<double>("scores", (size_t)P.Tl * N);
+    DSC_HIP(hipMemsetAsync(P.scores, 0xFF, (size_t)P.Tl * N * 8, st));
+    Ops ops{P.Vf, P.Rf, ldn};
+
+    // operand features and unary candidates of the streamed rung: exact scores
+    std::vector<ListItem> items;
+    for (int32_t c = 0; c < Mc; c++) items.push_back({sp.mat_raw[c], 0, OP_NONE, c, -1});
+    const int R = sp.streamed;
+    const int Bq = sp.B > 0 ? sp.B : 1;
+    if (R) {
+        const int32_t c0 = sp.rung_start[R - 1], c1 = sp.rung_start[R];
+        std::vector<int32_t> tmp(Bq);
+        for (int o = 0; o < OP_ADD; o++) {
+            if (sd.block[R][o] < 0) continue;
+            for (int32_t c = c0; c < c1; c++)
+                if (unit_rule(o, sp.B, &sp.mat_unit[(size_t)c * Bq], nullptr, tmp.data()))
+                    items.push_back({unary_id(sd, R, o, sp.mat_raw[c]), 1, o, c, -1});
+        }
+    }
+    ListItem* d_items = ctx->buf<ListItem>("items", items.size());
+    upload(d_items, items, st);
+    {
+        KTimer kt(ctx, st, "screen_list");
+        k_score_list<<<(unsigned)cdiv((int64_t)items.size(), 4), 256, 0, st>>>(
+            d_items, (int64_t)items.size(), ops, P.valid, n, pb.T, prm.score_mode, P.Yc, P.syy, N,
+            P.scores, P.nscored);
+        check_launch("k_score_list");
+    }
+    if (!R) return;
+
+    // streamed binary candidates
+    P.Vs = ctx->buf<double>("Vs", (size_t)n * ldm);
+    P.Rs = ctx->buf<double>("Rs", (size_t)n * ldm);
+    P.Cs = ctx->buf<double>("Cs", (size_t)n * ldm);
+    {
+        dim3 g((unsigned)cdiv(n, 32), (unsigned)cdiv(Mc, 32)), b(32, 8);
+        k_transpose<<<g, b, 0, st>>>(n, Mc, ldn, ldm, P.Vf, P.Vs);
+        k_transpose<<<g, b, 0, st>>>(n, Mc, ldn, ldm, P.Rf, P.Rs);
+        k_transpose<<<g, b, 0, st>>>(n, Mc, ldn, ldm, P.Cf, P.Cs);
+        check_launch("k_transpose");
+    }
+    uint32_t bin = 0;
+    for (int o = OP_ADD; o <= OP_RDIV; o++)
+        if (sd.block[R][o] >= 0) bin |= 1u << (o - OP_ADD);
+    if (!bin) return;
+    const int32_t jc0 = sp.rung_start[R - 1], jc1 = sp.rung_start[R];
+    const int pool = sd.pool[R];
+    const int32_t i_end = pool == R - 1 ? Mc : sp.rung_start[pool + 1];
+
+    PairArgs a{};
+    a.n = n; a.ldm = ldm; a.ldn = ldn; a.Mc = Mc; a.jc_end = jc1; a.i_end = i_end;
+    a.Vs = P.Vs; a.Rs = P.Rs; a.Cs = P.Cs; a.Vf = P.Vf; a.Rf = P.Rf; a.Cf = P.Cf;
+    a.mu = P.mu; a.mur = P.mur; a.valid = P.valid; a.mat_raw = P.mat_raw;
+    a.Yn = P.Yn; a.ysum = P.ysum; a.T = pb.T; a.mode = prm.score_mode; a.r = R;
+    a.sd = sd; a.N = N; a.scores = P.scores; a.nscored = P.nscored;
+    a.fix_cap = std::min<int64_t>(N, (int64_t)1 << 24);
+    a.fix_ids = ctx->buf<int64_t>("fix_ids", a.fix_cap);
+    a.fix_cnt = ctx->buf<unsigned long long>("fix_cnt", 1);
+    DSC_HIP(hipMemsetAsync(a.fix_cnt, 0, 8, st));
+
+    // dense tiles: all pairs (no units) or the multiplicative class (units)
+    const bool units = sp.B > 0;
+    const uint32_t dense_ops = units ? (bin & 28u) : bin;
+    const uint32_t list_ops = units ? (bin & 3u) : 0u;
+    if (dense_ops) {
+        const int J = dense_J(P.TP);
+        std::vector<int2> tiles;
+        for (int32_t j = jc0; j < jc1; j += J) {
+            const int32_t ilim = std::min<int32_t>(i_end, std::min<int32_t>(j + J - 1, jc1 - 1));
+            for (int32_t i0 = 0; i0 < ilim; i0 += 64) tiles.push_back(make_int2(j, i0));
+        }
+        int2* d_t = ctx->buf<int2>("tiles", tiles.size());
+        upload(d_t, tiles, st);
+        a.tiles = d_t;
+        a.ilist = nullptr;
+        a.icount = nullptr;
+        a.n_tiles = (int64_t)tiles.size();
+        a.opmask = dense_ops;
+        const int cls = units ? 28 : 31;
+        KTimer kt(ctx, st, "screen_pairs");
+        launch_pairs(cls, a, false, P.TP, st);
+        check_launch("k_screen_pairs");
+    }
+    if (list_ops) {
+        // same-unit partners below j (or inside the partner pool)
+        std::vector<int2> tiles;
+        std::vector<int32_t> il, ic;
+        std::map<std::string, std::vector<int32_t>> by_unit;
+        auto key = [&](int32_t c) {
+            return std::string((const char*)&sp.mat_unit[(size_t)c * Bq], sizeof(int32_t) * Bq);
+        };
+        if (pool != R - 1)
+            for (int32_t c = 0; c < i_end; c++) by_unit[key(c)].push_back(c);
+        for (int32_t c = 0; c < jc1; c++) {
+            if (c >= jc0) {
+                auto it = by_unit.find(key(c));
+                if (it != by_unit.end()) {
+                    const auto& v = it->second;
+                    for (size_t q = 0; q < v.size(); q += 64) {
+                        tiles.push_back(make_int2(c, (int)il.size()));
+                        const int cnt = (int)std::min<size_t>(64, v.size() - q);
+                        ic.push_back(cnt);
+                        il.insert(il.end(), v.begin() + q, v.begin() + q + cnt);
+                    }
+                }
+            }
+            if (pool == R - 1) by_unit[key(c)].push_back(c);
+        }
+        if (!tiles.empty()) {
+            int2* d_t = ctx->buf<int2>("ltiles", tiles.size());
+            int32_t* d_il = ctx->buf<int32_t>("ilist", il.size());
+            int32_t* d_ic = ctx->buf<int32_t>("icount", ic.size());
+            upload(d_t, tiles, st);
+            upload(d_il, il, st);
+            upload(d_ic, ic, st);
+            a.tiles = d_t;
+            a.ilist = d_il;
+            a.icount = d_ic;
+            a.n_tiles = (int64_t)tiles.size();
+            a.opmask = list_ops;
+            KTimer kt(ctx, st, "screen_pairs_list");
+            launch_pairs(3, a, true, P.TP, st);
+            check_launch("k_screen_pairs(list)");
+        }
+    }
+    // exact decision for the ill-conditioned ones (grid sized by the capacity,
+    // each wave exits when beyond the device-side count)
+    const unsigned long long nfix = download1(a.fix_cnt, st);
+    if (nfix > 0) {
+        const int64_t m = std::min<int64_t>((int64_t)nfix, a.fix_cap);
+        KTimer kt(ctx, st, "screen_fixup");
+        k_fixup<DISCOVER_MAX_TARGETS><<<(unsigned)cdiv(m, 4), 256, 0, st>>>(
+            a.fix_ids, a.fix_cnt, a.fix_cap, sd, sp.streamed, P.raw2c, P.valid, ops, n, pb.T,
+            prm.score_mode, P.Yc, P.syy, N, P.scores, P.nscored);
+        check_launch("k_fixup");
+    }
+}
+
+// Exact top-k of list t (pool, rescore, sort, duplicate groups).  The
+// pool holds every candidate whose score can reach the K-th largest
+// approximate score minus the error margin; it is rescored exactly and
+// scanned in (-score, ID) order.  If the scan leaves the region the pool
+// covers before k groups are final, K grows and the selection repeats.
+static void select_list(discover_ctx* ctx, const discover_problem& pb,
+                        const discover_screen_params& prm, Problem& P, int t, double margin,
+                        int64_t* out_ids, double* out_sc, discover_screen_stats& stats,
+                        hipStream_t st) {
+    const Space& sp = P.sp;
+    const int64_t N = sp.n_raw();
+    const double* sc = P.scores + (int64_t)t * N;
+    const int k = prm.k;
+    int64_t K = 2 * (int64_t)k + pb.n_exclude + 64;
+    uint32_t* hist = ctx->buf<uint32_t>("hist", 4096);
+    uint32_t* sel = ctx->buf<uint32_t>("sel", 4);
+    int64_t* stv = ctx->buf<int64_t>("selst", 2);
+    unsigned long long* cnt = ctx->buf<unsigned long long>("poolcnt", 1);
+    int64_t* res = ctx->buf<int64_t>("groupres", 3);
+    Ops ops{P.Vf, P.Rf, P.ldn};
+    const unsigned hb = (unsigned)std::min<int64_t>(1024, std::max<int64_t>(1, cdiv(N, 256 * 8)));
+    for (;;) {
+        {
+            KTimer kt(ctx, st, "select");
+            radix_select(sc, N, K, hist, sel, stv, st);
+        }
+        int64_t cap = 4 * K + 65536;
+        int64_t P_n = 0;
+        int64_t* pool = nullptr;
+        for (;;) {
+            pool = ctx->buf<int64_t>("pool", cap);
+            DSC_HIP(hipMemsetAsync(cnt, 0, 8, st));
+            k_compact<<<hb, 256, 0, st>>>(sc, N, sel, stv, margin, cap, pool, cnt);
+            check_launch("k_compact");
+            P_n = (int64_t)download1(cnt, st);
+            if (P_n <= cap) break;
+            cap = P_n;
+        }
+        stats.pool_size += P_n;
+        double* ps = ctx->buf<double>("ps", P_n);
+        uint8_t* pex = ctx->buf<uint8_t>("pex", P_n);
+        int32_t* order = ctx->buf<int32_t>("order", P_n);
+        int32_t* lo = ctx->buf<int32_t>("wlo", P_n);
+        int32_t* wc = ctx->buf<int32_t>("wcnt", P_n);
+        int64_t* off = ctx->buf<int64_t>("woff", P_n + 1);
+        if (P_n > 0) {
+            KTimer kt(ctx, st, "rescore");
+            k_rescore<DISCOVER_MAX_TARGETS><<<(unsigned)cdiv(P_n, 4), 256, 0, st>>>(
+                pool, P_n, sp.d, sp.streamed, P.raw2c, P.valid, ops, P.n, P.T, prm.score_mode, t,
+                P.Yc, P.syy, pb.exclude, pb.exclude ? pb.n_exclude : 0, ps, pex);
+            check_launch("k_rescore");
+        }
+        int64_t npairs = 0;
+        {
+            KTimer kt(ctx, st, "sort_dedup");
+            if (P_n > 0) {
+                k_rank<<<(unsigned)cdiv(P_n, 256), 256, 0, st>>>(ps, pool, P_n, order);
+                k_window<<<(unsigned)cdiv(P_n, 256), 256, 0, st>>>(ps, order, P_n, lo, wc);
+                k_scan_offsets<<<1, 1024, 0, st>>>(wc, P_n, off);
+                check_launch("k_rank");
+                npairs = download1(off + P_n, st);
+            }
+        }
+        uint8_t* flag = ctx->buf<uint8_t>("dupflag", npairs);
+        if (npairs > 0 && prm.dedup) {
+            KTimer kt(ctx, st, "dedup_pairs");
+            k_pairs<<<(unsigned)cdiv(npairs, 4), 256, 0, st>>>(pool, order, lo, off, P_n, sp.d,
+                                                               sp.streamed, P.raw2c, ops, P.n, flag);
+            check_launch("k_pairs");
+        }
+        int32_t* hpos = ctx->buf<int32_t>("hpos", P_n + 1);
+        uint8_t* hblk = ctx->buf<uint8_t>("hblk", P_n + 1);
+        int64_t* hmin = ctx->buf<int64_t>("hmin", P_n + 1);
+        double* hsc = ctx->buf<double>("hsc", P_n + 1);
+        k_groups<<<1, 64, 0, st>>>(pool, ps, pex, order, lo, off, flag, P_n, k, prm.dedup, sel,
+                                   stv, margin, hpos, hblk, hmin, hsc, out_ids, out_sc, res);
+        check_launch("k_groups");
+        int64_t h_res[3];
+        DSC_HIP(hipMemcpyAsync(h_res, res, sizeof h_res, hipMemcpyDeviceToHost, st));
+        DSC_HIP(hipStreamSynchronize(st));
+        if (h_res[1] || K >= N) {
+            stats.n_selected += h_res[0];
+            stats.n_merged += h_res[2];
+            return;
+        }
+        stats.pool_rounds += 1;
+        K = std::min<int64_t>(N, K * 4);
+    }
+}
+
+static void validate(const discover_problem* probs, int32_t nb, const discover_screen_params* prm,
+                     const int64_t* out_ids, const double* out_sc, const double* out_values,
+                     int64_t ldv) {
+    DSC_REQUIRE(probs && prm && nb >= 1, "probs/prm must be non-NULL and n_problems >= 1");
+    DSC_REQUIRE(out_ids && out_sc, "out_ids and out_scores are required");
+    DSC_REQUIRE(prm->rung >= 0 && prm->rung <= DISCOVER_MAX_RUNG, "rung %d outside 0..3", prm->rung);
+    DSC_REQUIRE(prm->k >= 1, "k must be >= 1");
+    DSC_REQUIRE((prm->ops & ~DISCOVER_OPS_ALL) == 0, "unknown operator bits 0x%x", prm->ops);
+    DSC_REQUIRE(prm->score_mode == DISCOVER_SCORE_PER_TARGET || prm->score_mode == DISCOVER_SCORE_MAX,
+                "score_mode %d", prm->score_mode);
+    DSC_REQUIRE(prm->precision >= DISCOVER_FP64 && prm->precision <= DISCOVER_FP16_GUARD,
+                "precision %d", prm->precision);
+    for (int r = 1; r <= prm->rung; r++) {
+        DSC_REQUIRE((prm->rung_ops[r] & ~DISCOVER_OPS_ALL) == 0, "unknown operator bits at rung %d", r);
+        DSC_REQUIRE(prm->rung_pool[r] >= -1 && prm->rung_pool[r] < r, "rung_pool[%d]", r);
+    }
+    for (int b = 0; b < nb; b++) {
+        const discover_problem& p = probs[b];
+        DSC_REQUIRE(p.n >= 3, "problem %d: n = %d < 3", b, p.n);
+        DSC_REQUIRE(p.p >= 1 && p.p <= 4096, "problem %d: p = %d", b, p.p);
+        DSC_REQUIRE(p.T >= 1 && p.T <= DISCOVER_MAX_TARGETS, "problem %d: T = %d", b, p.T);
+        DSC_REQUIRE(p.B >= 0 && p.B <= DISCOVER_MAX_UNITS, "problem %d: B = %d", b, p.B);
+        DSC_REQUIRE(p.B == 0 || p.units, "problem %d: units required when B > 0", b);
+        DSC_REQUIRE(p.X && p.Y, "problem %d: X and Y are required", b);
+        DSC_REQUIRE(p.ldx >= p.n && p.ldy >= p.n, "problem %d: ldx/ldy < n", b);
+        DSC_REQUIRE(p.n_exclude >= 0 && (p.n_exclude == 0 || p.exclude), "problem %d: exclude", b);
+        DSC_REQUIRE(!out_values || ldv >= p.n, "problem %d: ldv < n", b);
+    }
+}
+
+}  // namespace dsc
+
+extern "C" discover_status discover_generate_screen(discover_ctx* ctx, const discover_problem* probs,
+                                                    int32_t n_problems,
+                                                    const discover_screen_params* prm,
+                                                    int64_t* out_ids, double* out_scores,
+                                                    double* out_values, int64_t ldv,
+                                                    discover_screen_stats* out_stats, void* stream) {
+    using namespace dsc;
+    return guarded([&] {
+        DSC_REQUIRE(ctx, "ctx is NULL");
+        validate(probs, n_problems, prm, out_ids, out_scores, out_values, ldv);
+        DSC_HIP(hipSetDevice(ctx->device));
+        hipStream_t st = (hipStream_t)stream;
+        if (prm->precision != DISCOVER_FP64)
+            DSC_FAIL(DISCOVER_E_UNSUPPORTED, "reduced-precision screening is not built in this library");
+        int64_t row = 0;
+        for (int b = 0; b < n_problems; b++) {
+            const discover_problem& pb = probs[b];
+            Problem P{};
+            discover_screen_stats stats{};
+            screen_problem(ctx, pb, *prm, P, st);
+            stats.n_raw = P.sp.n_raw();
+            stats.n_unit_valid = P.sp.n_unit_valid;
+            const double margin = 4.0 * P.n * EPS64 * KAPPA_MAX;
+            const int Tl = P.Tl;
+            for (int t = 0; t < Tl; t++) {
+                select_list(ctx, pb, *prm, P, t, margin, out_ids + (row + t) * prm->k,
+                            out_scores + (row + t) * prm->k, stats, st);
+            }
+            if (out_values) {
+                KTimer kt(ctx, st, "values");
+                Ops ops{P.Vf, P.Rf, P.ldn};
+                const int64_t m = (int64_t)Tl * prm->k;
+                k_values<<<(unsigned)cdiv(m, 4), 256, 0, st>>>(out_ids + row * prm->k, m, P.sp.d,
+                                                               P.sp.streamed, P.raw2c, ops, P.n,
+                                                               out_values + row * prm->k * ldv, ldv);
+                check_launch("k_values");
+            }
+            stats.n_scored = (int64_t)download1(P.nscored, st);
+            DSC_HIP(hipStreamSynchronize(st));
+            ctx->resolve_timing();
+            if (out_stats) out_stats[b] = stats;
+            row += Tl;
+        }
+    });
+}

@@ -1,0 +1,107 @@
+// Candidate search space of the GPU path: rung sizes, ID arithmetic, unit
+// rules and the compacted set of operand features kept in HBM.
+//
+// The paper generates candidates iteratively from primary features and an
+// operator library (Software Description) and prunes dimensionally invalid
+// expressions early (Physics-Informed Constraints).  IDs are positions in
+// the canonical list described in include/discover.h; the GPU computes them
+// arithmetically from (rung, operator, operand indices).
+#pragma once
+
+#include "dsc_common.h"
+
+namespace dsc {
+
+enum : int {
+    OP_EXP = 0, OP_LOG, OP_SQRT, OP_SQ, OP_INV,
+    OP_ADD, OP_SUB, OP_MUL, OP_DIV, OP_RDIV,
+    OP_NONE = 15
+};
+
+// Plain-old-data view passed to kernels by value.
+struct SpaceDev {
+    int32_t p, R;
+    int32_t pool[4];          // partner rung of binary operators at rung r
+    uint32_t ops[4];          // operator mask of rung r
+    int64_t L[4];             // raw size of rung r
+    int64_t off[5];           // first raw index of rung r (off[R+1] = |P_R|)
+    int64_t npairs[4];        // pairs per binary block at rung r
+    int64_t block[4][10];     // first ID of operator block o at rung r (-1: disabled)
+};
+
+// ID of a binary candidate (op o, operands i < j raw) at rung r.
+__host__ __device__ inline int64_t pair_id(const SpaceDev& s, int r, int o, int64_t i, int64_t j) {
+    int64_t local = (s.pool[r] == r - 1)
+                        ? (choose2(j) - choose2(s.off[r - 1]) + i)
+                        : ((j - s.off[r - 1]) * s.off[s.pool[r] + 1] + i);
+    return s.block[r][o] + local;
+}
+
+__host__ __device__ inline int64_t unary_id(const SpaceDev& s, int r, int o, int64_t a) {
+    return s.block[r][o] + (a - s.off[r - 1]);
+}
+
+// Decode an ID into (rung, op, a, b); a = unary operand or i, b = j or -1.
+__host__ __device__ inline void decode_id(const SpaceDev& s, int64_t id, int& rung, int& op,
+                                          int64_t& a, int64_t& b) {
+    if (id < s.p) {
+        rung = 0; op = OP_NONE; a = id; b = -1;
+        return;
+    }
+    int r = 1;
+    while (r < s.R && id >= s.off[r + 1]) r++;
+    rung = r;
+    for (int o = 9; o >= 0; o--) {
+        if (s.block[r][o] < 0 || id < s.block[r][o]) continue;
+        int64_t q = id - s.block[r][o];
+        op = o;
+        if (o < OP_ADD) {
+            a = s.off[r - 1] + q; b = -1;
+            return;
+        }
+        if (s.pool[r] == r - 1) {
+            int64_t Q = q + choose2(s.off[r - 1]);
+            int64_t j = (int64_t)((1.0 + sqrt(1.0 + 8.0 * (double)Q)) * 0.5);
+            while (j > 1 && choose2(j) > Q) j--;
+            while (choose2(j + 1) <= Q) j++;
+            a = Q - choose2(j); b = j;
+        } else {
+            int64_t w = s.off[s.pool[r] + 1];
+            a = q % w; b = s.off[r - 1] + q / w;
+        }
+        return;
+    }
+    op = OP_NONE; a = -1; b = -1;   // unreachable for valid IDs
+}
+
+// Host description of one search space plus the operand features that are
+// materialised in HBM (all unit-legal features of rungs below the streamed
+// rung; for rung 0 the primaries themselves).
+struct Space {
+    SpaceDev d{};
+    int B = 0;
+    int streamed = 0;                  // rung whose candidates are streamed (0: none)
+    int64_t M_raw = 0;                 // raw features below the streamed rung
+    std::vector<int64_t> mat_raw;      // compact -> raw index (ascending)
+    std::vector<int32_t> raw2c;        // raw -> compact or -1 (size M_raw)
+    std::vector<int8_t> mat_op;        // per compact feature: operator (OP_NONE for primaries)
+    std::vector<int32_t> mat_a, mat_b; // compact operand indices (-1 if none)
+    std::vector<int32_t> mat_unit;     // compact x B exponents scaled by 2^R
+    std::vector<int32_t> rung_start;   // compact start of each materialised rung, + end
+    int64_t n_unit_valid = 0;          // over all of P_R
+    int64_t n_unit_valid_streamed = 0;
+
+    int64_t n_raw() const { return d.off[d.R + 1]; }
+    int32_t Mc() const { return (int32_t)mat_raw.size(); }
+};
+
+// Build the space; `units` is host [p][B] (may be NULL when B = 0).
+void build_space(Space& sp, int p, const discover_screen_params& prm, int B,
+                 const int32_t* units);
+
+// Host-side unit rule (exponents scaled by 2^R); returns legality.
+bool unit_rule(int op, int B, const int32_t* ua, const int32_t* ub, int32_t* out);
+
+std::string expr_of(const SpaceDev& s, int64_t id);
+
+}  // namespace dsc

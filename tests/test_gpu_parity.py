@@ -1,0 +1,278 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle on
+the same seeded inputs.
+
+Bar (see the design doc for the derivation):
+  * selected candidate IDs, unit-prune counts and L0 winners: identical;
+    where the oracle itself has a near-tie (|delta s| <= 1e-12 s at the
+    cut, not a duplicate) either member is accepted;
+  * scores: |s_gpu - s_oracle| <= 1e-10 s_oracle;
+  * RMSE: <= 1e-10 relative (+1e-13 std(y) absolute);
+  * coefficients: <= 1e-10 relative to the largest |coef| of the model.
+"""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+S_RTOL = 1e-10
+TIE = 1e-12
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ctx(torch):
+    import paper_2602_06986_amd as D
+    c = D.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def D():
+    import paper_2602_06986_amd as D
+    return D
+
+
+def dev(torch, a, dtype=None):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def prm_of(D, w, k=None, dedup=True, mode=None):
+    return D.params(ops=w["ops"], rung=w["rung"], k=k or w["k"],
+                    score_mode=D.SCORE_MAX if (mode or w["score_mode"]) == "max" else D.SCORE_PER_TARGET,
+                    dedup=dedup, rung_ops=w.get("rung_ops"), rung_pool=w.get("rung_pool"))
+
+
+def check_selection(g_ids, g_sc, o_ids, o_sc, all_scores=None, what=""):
+    """Identical lists up to documented near-ties; scores within S_RTOL."""
+    g_ids = [int(i) for i in g_ids if i >= 0]
+    o_ids = [int(i) for i in o_ids]
+    assert len(g_ids) == len(o_ids), (what, len(g_ids), len(o_ids))
+    o_map = dict(zip(o_ids, o_sc))
+    g_map = dict(zip(g_ids, g_sc[:len(g_ids)]))
+    if set(g_ids) != set(o_ids):
+        sk = min(o_sc)
+        extra = set(g_ids) - set(o_ids)
+        missing = set(o_ids) - set(g_ids)
+        for i in missing:
+            assert o_map[i] <= sk * (1 + TIE), (what, "missing", i, o_map[i], sk)
+        for i in extra:
+            assert all_scores is not None and abs(all_scores[i] - sk) <= TIE * sk, (what, "extra", i)
+    for a, b in zip(g_ids, o_ids):
+        if a != b:
+            assert abs(g_map[a] - o_map.get(b, g_map[a])) <= TIE * max(g_map[a], 1e-300) * 10, \
+                (what, "order", a, b)
+    for i in set(g_ids) & set(o_ids):
+        assert abs(g_map[i] - o_map[i]) <= S_RTOL * o_map[i], (what, i, g_map[i], o_map[i])
+
+
+def check_model(g_sub_ids, g_rmse, g_coef, o_model, y, what=""):
+    assert tuple(sorted(g_sub_ids)) == tuple(sorted(o_model["ids"])), (what, g_sub_ids, o_model["ids"])
+    assert abs(g_rmse - o_model["rmse"]) <= 1e-10 * o_model["rmse"] + 1e-13 * np.std(y), \
+        (what, g_rmse, o_model["rmse"])
+    # order coefficients by ID for comparison (both sides: intercept first)
+    order_g = np.argsort(g_sub_ids)
+    order_o = np.argsort(o_model["ids"])
+    cg = np.concatenate([[g_coef[0]], np.asarray(g_coef[1:])[order_g]])
+    co = np.concatenate([[o_model["coef"][0]], np.asarray(o_model["coef"][1:])[order_o]])
+    scale = np.max(np.abs(co))
+    assert np.max(np.abs(cg - co)) <= 1e-10 * scale, (what, cg, co)
+
+
+def run_both(torch, ctx, D, O, w, l0_mode="auto"):
+    ref = O.sisso(w, l0_mode=l0_mode)
+    X = dev(torch, w["X"])
+    y = dev(torch, w["Y"][0])
+    got = ctx.sisso(X, y, prm_of(D, w), w["D"], units=w["units"], n_resid=w["n_resid"],
+                    omp_D=w["omp_D"])
+    return ref, got
+
+
+def compare_sisso(ref, got, w, what):
+    y = w["Y"][0]
+    S_g = got["S_ids"].cpu().numpy()
+    for d, (rd, gd) in enumerate(zip(ref["dims"], got["dims"])):
+        check_selection(gd["sel_ids"].cpu().numpy(), gd["sel_scores"].cpu().numpy(),
+                        rd["sel_ids"], rd["sel_scores"], what="%s dim %d" % (what, d + 1))
+        st = gd["screen_stats"]
+        assert st["n_raw"] == ref["space"].N
+        assert st["n_unit_valid"] == int((rd["status"] != 1).sum()), (st, what)
+        assert st["n_scored"] == rd["nvalid"], (st["n_scored"], rd["nvalid"], what)
+        subs = gd["subsets"].cpu().numpy()
+        for q, mo in enumerate(rd["models"]):
+            ids_g = [int(S_g[i]) for i in subs[q]]
+            check_model(ids_g, float(gd["rmse"][q]), gd["coef"][q].cpu().numpy(), mo, y,
+                        "%s dim %d model %d" % (what, d + 1, q))
+
+
+# ---------------------------------------------------------------- SISSO loops
+@pytest.mark.parametrize("name", ["tiny", "tiny_r2"])
+def test_sisso_small(torch, ctx, D, oracle_mod, name):
+    import synth
+    w = synth.make(name)
+    ref, got = run_both(torch, ctx, D, oracle_mod, w)
+    compare_sisso(ref, got, w, name)
+
+
+def test_sisso_units16_full_size(torch, ctx, D, oracle_mod):
+    """The 16-feature, 3-unit, rung-2 workload at full size (n=500,
+    k=500 per dimension, L0 D<=3 over the 1500-feature union)."""
+    import synth
+    w = synth.units16()
+    ref, got = run_both(torch, ctx, D, oracle_mod, w)
+    compare_sisso(ref, got, w, "units16")
+    assert got["dims"][0]["screen_stats"]["n_unit_valid"] == 336214
+    assert got["dims"][2]["l0_stats"]["n_subsets"] == math.comb(1500, 3)
+
+
+# ---------------------------------------------------------------- screening
+def test_multitarget_per_target(torch, ctx, D, oracle_mod):
+    import synth
+    O = oracle_mod
+    w = synth.multitarget16()
+    sp = O.Space.of(w)
+    (lists), status, nvalid = O.sis(sp, w["X"], None, w["Y"], w["k"], (), "per_target")
+    ids, sc, vals, st = ctx.generate_screen(dev(torch, w["X"]), dev(torch, w["Y"]),
+                                            prm_of(D, w, mode="per_target"))
+    assert ids.shape == (16, 20)
+    for t in range(16):
+        check_selection(ids[t].cpu().numpy(), sc[t].cpu().numpy(), lists[t][0], lists[t][1],
+                        what="target %d" % t)
+    # the returned values are the selected features' values
+    V, _ = O.values(sp, w["X"], None, ids[3].cpu().numpy())
+    np.testing.assert_allclose(vals[3].cpu().numpy(), V, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("seed,p,n,B,R,dedup,k", [
+    (0, 5, 37, 0, 2, True, 7), (1, 7, 129, 2, 2, True, 40), (2, 4, 64, 0, 2, False, 25),
+    (3, 6, 65, 3, 2, True, 300), (4, 3, 20, 1, 1, True, 50), (5, 9, 200, 0, 1, True, 10),
+    (6, 5, 3, 0, 1, True, 5)])
+def test_screen_random(torch, ctx, D, oracle_mod, seed, p, n, B, R, dedup, k):
+    """Ragged sizes (n and operand counts off the 64 grid), units on/off,
+    duplicates on/off, k beyond the number of valid candidates."""
+    O = oracle_mod
+    rng = np.random.default_rng(100 + seed)
+    X = rng.lognormal(0, 0.4, size=(p, n))
+    units = rng.integers(-1, 2, size=(p, B)).astype(np.int32) if B else None
+    if B:
+        units[: max(1, p // 3)] = 0
+    y = X[0] * X[-1] + 0.3 * X[1 % p] + 0.05 * rng.normal(size=n)
+    sp = O.Space(p, R, O.OPS)
+    (lst,), status, nvalid = O.sis(sp, X, units, y[None], k, (), "per_target", dedup)
+    ids, sc, vals, st = ctx.generate_screen(dev(torch, X), dev(torch, y[None]),
+                                            D.params(rung=R, k=k, dedup=dedup), units=units)
+    check_selection(ids[0].cpu().numpy(), sc[0].cpu().numpy(), lst[0], lst[1], what="seed %d" % seed)
+    assert st["n_unit_valid"] == int((status != O.ST_UNIT).sum())
+    assert st["n_scored"] == nvalid
+    n_sel = int((ids[0] >= 0).sum())
+    assert n_sel == len(lst[0])
+    if n_sel < k:
+        assert bool((ids[0][n_sel:] == -1).all())
+
+
+def test_screen_exclusion(torch, ctx, D, oracle_mod):
+    """IDs already in the subspace and their duplicate groups are not
+    selected again."""
+    import synth
+    O = oracle_mod
+    w = synth.tiny(rung=2)
+    sp = O.Space.of(w)
+    (first,), _, _ = O.sis(sp, w["X"], None, w["Y"], 20)
+    excl = first[0][:7]
+    (lst,), _, _ = O.sis(sp, w["X"], None, w["Y"], 20, excl)
+    ids, sc, _, _ = ctx.generate_screen(dev(torch, w["X"]), dev(torch, w["Y"]), prm_of(D, w),
+                                        exclude=dev(torch, excl, torch.int64))
+    check_selection(ids[0].cpu().numpy(), sc[0].cpu().numpy(), lst[0], lst[1], what="exclude")
+    assert not set(excl) & set(ids[0].cpu().numpy().tolist())
+
+
+def test_screen_errors(torch, ctx, D):
+    X = dev(torch, np.random.default_rng(0).uniform(0.5, 2, size=(4, 30)))
+    with pytest.raises(D.DiscoverError) as e:
+        ctx.generate_screen(X, dev(torch, np.ones((1, 30))), D.params(rung=1, k=5))
+    assert e.value.code == -5
+    with pytest.raises(D.DiscoverError) as e:
+        ctx.generate_screen(X, dev(torch, np.arange(30.0)[None]), D.params(rung=5, k=5))
+    assert e.value.code == -1
+    with pytest.raises(D.DiscoverError) as e:
+        ctx.generate_screen(X, dev(torch, np.arange(30.0)[None]), D.params(rung=1, k=0))
+    assert e.value.code == -1
+
+
+# ---------------------------------------------------------------- L0 / OMP
+def _design(rng, S, n, corr=0.5):
+    base = rng.normal(size=(3, n))
+    F = rng.normal(size=(S, n)) + corr * base[rng.integers(0, 3, size=S)]
+    return F * rng.uniform(0.5, 3.0, size=(S, 1)) + rng.normal(size=(S, 1))
+
+
+@pytest.mark.parametrize("Dd,S,n,m", [(1, 70, 97, 3), (2, 70, 97, 3), (3, 70, 97, 3), (3, 131, 50, 1),
+                                      (2, 5, 7, 4), (3, 3, 6, 1), (3, 200, 301, 8)])
+def test_l0_against_oracle(torch, ctx, D, oracle_mod, Dd, S, n, m):
+    O = oracle_mod
+    rng = np.random.default_rng(S * 10 + Dd)
+    F = _design(rng, S, n)
+    y = 0.3 + F[S // 2] - 0.7 * F[S - 1] + 0.2 * F[0] + 0.1 * rng.normal(size=n)
+    ids = rng.permutation(10 ** 6)[:S].astype(np.int64)
+    ref = O.l0(F, ids, y, Dd, m=m, mode="direct")
+    sub, rmse, coef, res, st = ctx.l0_fit(dev(torch, F), dev(torch, ids), dev(torch, y), Dd, m)
+    assert st["n_subsets"] == math.comb(S, Dd)
+    for q, mo in enumerate(ref):
+        s = sub[q].cpu().numpy()
+        check_model([int(ids[i]) for i in s], float(rmse[q]), coef[q].cpu().numpy(), mo, y, "q%d" % q)
+        np.testing.assert_allclose(res[q].cpu().numpy(), mo["resid"], rtol=0,
+                                   atol=1e-10 * np.max(np.abs(mo["resid"])))
+    for q in range(len(ref), m):
+        assert int(sub[q][0]) == -1
+
+
+def test_l0_noise_free_planted(torch, ctx, D, oracle_mod):
+    """y = c0 + c1 f_a + c2 f_b exactly: winner {a, b}, RMSE ~ 0, planted
+    coefficients; at D = 3 every superset fits exactly and the smallest ID
+    tuple wins."""
+    rng = np.random.default_rng(42)
+    F = _design(rng, 60, 120)
+    y = 0.7 + 1.3 * F[17] - 2.1 * F[44]
+    ids = np.arange(60, dtype=np.int64) * 3 + 5
+    sub, rmse, coef, _, _ = ctx.l0_fit(dev(torch, F), dev(torch, ids), dev(torch, y), 2, 1)
+    assert sorted(sub[0].cpu().numpy().tolist()) == [17, 44]
+    assert float(rmse[0]) <= 1e-12 * np.std(y)
+    np.testing.assert_allclose(coef[0].cpu().numpy(), [0.7, 1.3, -2.1], rtol=1e-10)
+    ref = oracle_mod.l0(F, ids, y, 3, mode="direct")[0]
+    sub3, _, _, _, _ = ctx.l0_fit(dev(torch, F), dev(torch, ids), dev(torch, y), 3, 1)
+    assert sorted(ids[sub3[0].cpu().numpy()].tolist()) == sorted(ref["ids"])
+
+
+def test_l0_singular_rejected(torch, ctx, D):
+    rng = np.random.default_rng(3)
+    F = _design(rng, 8, 40)
+    F[5] = 2.0 * F[2] + 1.0
+    y = F[2] + F[6] + 0.01 * rng.normal(size=40)
+    ids = np.arange(8, dtype=np.int64)
+    sub, _, _, _, _ = ctx.l0_fit(dev(torch, F), dev(torch, ids), dev(torch, y), 2, 20)
+    for q in range(20):
+        s = set(sub[q].cpu().numpy().tolist())
+        assert s != {2, 5}
+
+
+@pytest.mark.parametrize("init", [None, (3, 9)])
+def test_omp_against_oracle(torch, ctx, D, oracle_mod, init):
+    O = oracle_mod
+    rng = np.random.default_rng(7)
+    F = _design(rng, 90, 150, corr=0.6)
+    y = 2 * F[3] - F[17] + 0.5 * F[8] + 0.3 * F[60] + 0.2 * rng.normal(size=150)
+    ids = np.arange(90, dtype=np.int64) + 1000
+    act_o, coef_o, rmse_o, res_o = O.omp(F, ids, y, 6, init or ())
+    it = None if init is None else dev(torch, np.array(init, np.int32), torch.int32)
+    act, coef, rmse, res = ctx.omp(dev(torch, F), dev(torch, ids), dev(torch, y), 6, it)
+    assert act.cpu().numpy().tolist() == act_o
+    np.testing.assert_allclose(coef.cpu().numpy(), coef_o, rtol=1e-10, atol=1e-10 * np.max(np.abs(coef_o)))
+    assert abs(float(rmse[0]) - rmse_o) <= 1e-10 * rmse_o
