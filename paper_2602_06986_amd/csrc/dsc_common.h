@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <string>
 #include <utility>
 #include <vector>
@@ -82,6 +83,7 @@ struct discover_ctx {
     };
     std::vector<Pending> pending;
     std::vector<hipEvent_t> free_events;
+    std::map<std::string, std::shared_ptr<void>> plans;   // cached search-space plans
 
     // Grow-only named device buffer of at least `bytes` bytes.
     void* raw(const std::string& name, size_t bytes) {

@@ -15,6 +15,8 @@
 //      data (one workgroup per subset) and ranked by RSS with the tie rule.
 #include "dsc_select.h"
 
+#include <algorithm>
+
 namespace dsc {
 
 constexpr double PIV_TOL = 1e-10;     // normalized Cholesky pivot at/below which a subset is singular
@@ -91,19 +93,17 @@ __global__ __launch_bounds__(256) void k_gram(int M, int ldz, int nk, const doub
 }
 
 // ----------------------------------------------------------------- sweep
+// Every sweep writes, per lane, the best explained fraction q of the
+// subsets that lane owns (D = 1, 2: exactly one subset per lane; D = 3: the
+// lane's (a, c) pair over all b, with b packed into the low 16 mantissa
+// bits).  A radix selection over these lane values gives the m-th best, and
+// only lanes reaching the band threshold are expanded again.
 struct SweepArgs {
     const double* G;
     int ldg, S, D;
-    const int2* items;        // (a, first c / b / a of the 64-lane block)
+    const int2* items;        // D = 1, 2: (a, first b) per wave; D = 3: (a, first c) per block
     int64_t n_items;
-    double* wbest;            // per item: best packed q (or -1)
-    int32_t* wlane;           // per item: the lane index of the best
-    // collect mode
-    double thr;
-    int4* band;               // (a, b, c, -) rows
-    double* bq;
-    unsigned long long* bcnt;
-    int64_t bcap;
+    double* lane_q;           // [n_items][64] (D = 1, 2) or [n_items][256] (D = 3)
 };
 
 __device__ __forceinline__ double pack_q(double q, int b) {
@@ -118,29 +118,7 @@ __device__ __forceinline__ double fast_rcp(double x) {
     return fma(r, e, r);
 }
 
-template <bool COLLECT>
-__device__ __forceinline__ void wave_finish(const SweepArgs& g, int64_t item, double best,
-                                            int lane) {
-    if (COLLECT) return;
-    const double mx = wave_max(best);
-    const unsigned long long hit = __ballot(best == mx);
-    const int who = __ffsll((long long)hit) - 1;
-    if (lane == 0) {
-        g.wbest[item] = mx;
-        g.wlane[item] = who;
-    }
-}
-
-__device__ __forceinline__ void band_push(const SweepArgs& g, int a, int b, int c, double q) {
-    const unsigned long long slot = atomicAdd(g.bcnt, 1ull);
-    if ((int64_t)slot < g.bcap) {
-        g.band[slot] = make_int4(a, b, c, 0);
-        g.bq[slot] = q;
-    }
-}
-
 // D = 1: lane a.
-template <bool COLLECT>
 __global__ __launch_bounds__(256) void k_sweep1(SweepArgs g) {
     const int64_t it = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (it >= g.n_items) return;
@@ -151,40 +129,32 @@ __global__ __launch_bounds__(256) void k_sweep1(SweepArgs g) {
         const double caa = g.G[(int64_t)a * g.ldg + a], ca = g.G[(int64_t)a * g.ldg + g.S];
         if (caa > PIV_TOL) q = ca * ca / caa;
     }
-    if (COLLECT) {
-        if (q >= g.thr) band_push(g, a, -1, -1, q);
-        return;
-    }
-    wave_finish<COLLECT>(g, it, q, lane);
+    g.lane_q[it * 64 + lane] = q;
 }
 
 // D = 2: fixed a per wave, lane b.
-template <bool COLLECT>
+__device__ __forceinline__ double q2(const double* G, int ldg, int S, int a, int b) {
+    const double* Ga = G + (int64_t)a * ldg;
+    const double caa = Ga[a], ca = Ga[S];
+    if (!(caa > PIV_TOL)) return -1.0;
+    const double cab = Ga[b], cbb = G[(int64_t)b * ldg + b], cb = G[(int64_t)b * ldg + S];
+    const double w = cab / caa;
+    const double piv = cbb - cab * w;
+    const double e = cb - ca * w;
+    return piv > PIV_TOL ? ca * ca / caa + e * e / piv : -1.0;
+}
+
 __global__ __launch_bounds__(256) void k_sweep2(SweepArgs g) {
     const int64_t it = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (it >= g.n_items) return;
     const int lane = threadIdx.x & 63;
     const int a = g.items[it].x, b = g.items[it].y + lane;
-    const double* Ga = g.G + (int64_t)a * g.ldg;
-    const double caa = Ga[a], ca = Ga[g.S];
-    double q = -1.0;
-    if (b < g.S && b > a && caa > PIV_TOL) {
-        const double cab = Ga[b], cbb = g.G[(int64_t)b * g.ldg + b], cb = g.G[(int64_t)b * g.ldg + g.S];
-        const double w = cab / caa;
-        const double piv = cbb - cab * w;
-        const double e = cb - ca * w;
-        if (piv > PIV_TOL) q = ca * ca / caa + e * e / piv;
-    }
-    if (COLLECT) {
-        if (q >= g.thr) band_push(g, a, b, -1, q);
-        return;
-    }
-    wave_finish<COLLECT>(g, it, q, lane);
+    g.lane_q[it * 64 + lane] = (b < g.S && b > a) ? q2(g.G, g.ldg, g.S, a, b) : -1.0;
 }
 
-// D = 3: fixed a per workgroup (4 waves = 4 consecutive c-blocks of 64),
-// lane c, loop over a < b < c.  Per b (uniform): u_b = G[a][b],
-// g_b = z'_b / d_b, h_b = 1 / d_b, Q_ab = c_a^2/G_aa + z'_b^2 / d_b with
+// D = 3: one block = fixed a and 256 consecutive c (4 waves, lane c), loop
+// over a < b < c.  Per b (uniform, staged in LDS): u_b = G[a][b],
+// g_b = z'_b / d_b, h_b = 1 / d_b, Q_ab = c_a^2 / G_aa + z'_b^2 / d_b with
 // d_b = G_bb - u_b^2 / G_aa and z'_b = c_b - u_b c_a / G_aa.  Per subset:
 //   C'  = G[b][c] - u_b u_c / G_aa
 //   den = d_c - C'^2 / d_b            (third Cholesky pivot)
@@ -192,71 +162,147 @@ __global__ __launch_bounds__(256) void k_sweep2(SweepArgs g) {
 //   q   = Q_ab + e^2 / den.
 constexpr int SW3_CHUNK = 1024;       // b entries staged in LDS at a time (32 KB)
 
-template <bool COLLECT>
+struct Sw3Lane {
+    double upc, dc, zc;
+};
+
+__device__ __forceinline__ double4 sw3_b_entry(const double* G, int ldg, int S, const double* Ga,
+                                               double ica, double ca, int b) {
+    const double ub = Ga[b];
+    const double db = G[(int64_t)b * ldg + b] - ub * ub * ica;
+    const double zb = G[(int64_t)b * ldg + S] - ub * ca * ica;
+    if (db > PIV_TOL) {
+        const double hb = 1.0 / db;
+        return make_double4(ub, zb * hb, hb, ca * ca * ica + zb * zb * hb);
+    }
+    return make_double4(ub, 0.0, 0.0, -1.0);            // singular pair: skipped
+}
+
+__device__ __forceinline__ double sw3_q(const double4& e, const Sw3Lane& L, double Cbc,
+                                        double& den) {
+    const double Cp = fma(-e.x, L.upc, Cbc);
+    const double ee = fma(-Cp, e.y, L.zc);
+    const double t = Cp * e.z;
+    den = fma(-Cp, t, L.dc);
+    return fma(ee * ee, fast_rcp(den), e.w);
+}
+
 __global__ __launch_bounds__(256) void k_sweep3(SweepArgs g) {
     __shared__ double4 tab[SW3_CHUNK];
-    const int64_t it0 = (int64_t)blockIdx.x * 4;
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t it = it0 + wv;
-    // the 4 waves of a block share a (items are grouped by a on the host)
-    const int a = g.items[min(it0, g.n_items - 1)].x;
+    const int2 item = g.items[blockIdx.x];
+    const int a = item.x;
+    double* out = g.lane_q + (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (a < 0) {                                         // padding block (uniform)
+        *out = -1.0;
+        return;
+    }
     const double* Ga = g.G + (int64_t)a * g.ldg;
     const double caa = Ga[a], ca = Ga[g.S];
+    const int c = item.y + threadIdx.x;
+    if (!(caa > PIV_TOL)) {                              // uniform
+        *out = -1.0;
+        return;
+    }
     const double ica = 1.0 / caa;
-    int cmax_blk = a + 1;
-    for (int w = 0; w < 4; w++)
-        if (it0 + w < g.n_items && g.items[it0 + w].x == a)
-            cmax_blk = max(cmax_blk, min(g.S, g.items[it0 + w].y + 64));
-    const bool active = it < g.n_items && g.items[it].x == a && caa > PIV_TOL;
-    const int c0 = active ? g.items[it].y : g.S;
-    const int c = c0 + lane;
-    const bool cok = active && c < g.S;
+    const bool cok = c < g.S;
     const int cc = cok ? c : a;
+    Sw3Lane L;
     const double uc = Ga[cc];
-    const double upc = uc * ica;
-    const double dc = g.G[(int64_t)cc * g.ldg + cc] - uc * upc;
-    const double zc = g.G[(int64_t)cc * g.ldg + g.S] - ca * upc;
-    const int bend = active ? min(g.S, c0 + 64) - 1 : a + 1;   // b < (largest c of the wave)
+    L.upc = uc * ica;
+    L.dc = g.G[(int64_t)cc * g.ldg + cc] - uc * L.upc;
+    L.zc = g.G[(int64_t)cc * g.ldg + g.S] - ca * L.upc;
+    const int wave_c0 = item.y + (threadIdx.x & ~63);
+    const int bend = min(g.S, wave_c0 + 64) - 1;         // b < the wave's largest c
+    const int bend_blk = min(g.S, item.y + 256) - 1;
     const double* colc = g.G + cc;
     double best = -1.0;
-    for (int b0 = a + 1; b0 < cmax_blk - 1; b0 += SW3_CHUNK) {
-        const int nb = min(SW3_CHUNK, cmax_blk - 1 - b0);
+    for (int b0 = a + 1; b0 < bend_blk; b0 += SW3_CHUNK) {
+        const int nb = min(SW3_CHUNK, bend_blk - b0);
         __syncthreads();
-        for (int t = threadIdx.x; t < nb; t += 256) {
-            const int b = b0 + t;
-            const double ub = Ga[b];
-            const double db = g.G[(int64_t)b * g.ldg + b] - ub * ub * ica;
-            const double zb = g.G[(int64_t)b * g.ldg + g.S] - ub * ca * ica;
-            double4 e;
-            if (db > PIV_TOL) {
-                const double hb = 1.0 / db;
-                e = make_double4(ub, zb * hb, hb, ca * ca * ica + zb * zb * hb);
-            } else {
-                e = make_double4(ub, 0.0, 0.0, -1.0);     // singular pair: skipped
-            }
-            tab[t] = e;
-        }
+        for (int t = threadIdx.x; t < nb; t += 256)
+            tab[t] = sw3_b_entry(g.G, g.ldg, g.S, Ga, ica, ca, b0 + t);
         __syncthreads();
         const int bl = min(b0 + nb, bend);
         for (int b = b0; b < bl; b++) {
             const double4 e = tab[b - b0];
             if (e.w < 0.0) continue;                      // uniform: singular (a, b)
-            const double Cbc = colc[(int64_t)b * g.ldg];
-            const double Cp = fma(-e.x, upc, Cbc);
-            const double ee = fma(-Cp, e.y, zc);
-            const double t = Cp * e.z;
-            const double den = fma(-Cp, t, dc);
-            double q = fma(ee * ee, fast_rcp(den), e.w);
+            double den;
+            const double q = sw3_q(e, L, colc[(int64_t)b * g.ldg], den);
             const bool ok = cok && (b < c) && (den > PIV_TOL);
-            if (COLLECT) {
-                if (ok && q >= g.thr) band_push(g, a, b, c, q);
-            } else {
-                q = ok ? pack_q(q, b) : -1.0;
-                best = fmax(best, q);
-            }
+            best = fmax(best, ok ? pack_q(q, b) : -1.0);
         }
     }
-    if (it < g.n_items) wave_finish<COLLECT>(g, it, best, lane);
+    *out = best;
+}
+
+// Band expansion.  thr = (m-th best lane value) * (1 - 1e-12) - GRAM_DELTA.
+struct BandArgs {
+    const double* G;
+    int ldg, S, D;
+    const int2* items;
+    int64_t n_lanes;
+    const double* lane_q;
+    const uint32_t* sel;
+    const int64_t* st;
+    int4* band;
+    unsigned long long* bcnt;
+    int64_t bcap;
+    int2* pairs;              // D = 3: (a, c) lanes to expand
+    unsigned long long* pcnt;
+    int64_t pcap;
+};
+
+__device__ __forceinline__ double band_thr(const BandArgs& g) {
+    if (g.st[1]) return -0.5;                            // fewer than m valid lanes: take all
+    return select_threshold(g.sel, g.st) * (1.0 - 1e-12) - GRAM_DELTA;
+}
+
+__device__ __forceinline__ void band_push(const BandArgs& g, int a, int b, int c) {
+    const unsigned long long slot = atomicAdd(g.bcnt, 1ull);
+    if ((int64_t)slot < g.bcap) g.band[slot] = make_int4(a, b, c, 0);
+}
+
+__global__ __launch_bounds__(256) void k_band_lanes(BandArgs g) {
+    const double thr = band_thr(g);
+    const int per = g.D == 3 ? 256 : 64;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < g.n_lanes;
+         i += (int64_t)gridDim.x * 256) {
+        const double q = g.lane_q[i];
+        if (!(q > -0.5) || q < thr - 1e-9) continue;
+        const int2 it = g.items[i / per];
+        const int lane = (int)(i % per);
+        if (g.D == 1) band_push(g, it.y + lane, -1, -1);
+        else if (g.D == 2) band_push(g, it.x, it.y + lane, -1);
+        else {
+            const unsigned long long slot = atomicAdd(g.pcnt, 1ull);
+            if ((int64_t)slot < g.pcap) g.pairs[slot] = make_int2(it.x, it.y + lane);
+        }
+    }
+}
+
+// D = 3: one thread per listed (a, c) lane, every b with q >= thr.
+__global__ __launch_bounds__(256) void k_band_expand3(BandArgs g) {
+    const double thr = band_thr(g);
+    const int64_t np = min((int64_t)*g.pcnt, g.pcap);
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < np;
+         i += (int64_t)gridDim.x * 256) {
+        const int a = g.pairs[i].x, c = g.pairs[i].y;
+        const double* Ga = g.G + (int64_t)a * g.ldg;
+        const double caa = Ga[a], ca = Ga[g.S];
+        const double ica = 1.0 / caa;
+        Sw3Lane L;
+        const double uc = Ga[c];
+        L.upc = uc * ica;
+        L.dc = g.G[(int64_t)c * g.ldg + c] - uc * L.upc;
+        L.zc = g.G[(int64_t)c * g.ldg + g.S] - ca * L.upc;
+        for (int b = a + 1; b < c; b++) {
+            const double4 e = sw3_b_entry(g.G, g.ldg, g.S, Ga, ica, ca, b);
+            if (e.w < 0.0) continue;
+            double den;
+            const double q = sw3_q(e, L, g.G[(int64_t)b * g.ldg + c], den);
+            if (den > PIV_TOL && q >= thr) band_push(g, a, b, c);
+        }
+    }
 }
 
 // ------------------------------------------------------------ QR refit
@@ -335,13 +381,16 @@ __device__ void block_lsq(int n, int d, const int* idx, const double* __restrict
 // One workgroup per band entry (persistent over the band).
 __global__ __launch_bounds__(256) void k_refit(int n, int D, const double* __restrict__ F,
                                                int64_t ldf, const double* __restrict__ y,
-                                               const int4* __restrict__ band, int64_t nb,
+                                               const int4* __restrict__ band,
+                                               const unsigned long long* __restrict__ bcnt,
+                                               int64_t bcap,
                                                double* __restrict__ scratch,
                                                double* __restrict__ brss,
                                                double* __restrict__ bcoef) {
     __shared__ double coef[DISCOVER_MAX_D + 1];
     __shared__ double rss;
     double* A = scratch + (int64_t)blockIdx.x * (D + 2) * n;
+    const int64_t nb = min((int64_t)*bcnt, bcap);
     for (int64_t e = blockIdx.x; e < nb; e += gridDim.x) {
         const int4 s = band[e];
         const int idx[3] = {s.x, s.y, s.z};
@@ -357,13 +406,15 @@ __global__ __launch_bounds__(256) void k_refit(int n, int D, const double* __res
 // Rank the band (one thread): repeatedly take the minimum RSS; entries
 // within TAU_TIE * yy of it are tied and the smallest sorted-ID tuple wins.
 __global__ void k_rank_models(const int4* __restrict__ band, const double* __restrict__ brss,
-                              const double* __restrict__ bcoef, int64_t nb, int D, int m,
+                              const double* __restrict__ bcoef,
+                              const unsigned long long* __restrict__ bcnt, int64_t bcap, int D, int m,
                               const int64_t* __restrict__ ids, const double* __restrict__ yyp,
                               int n, uint8_t* __restrict__ taken, int32_t* __restrict__ out_sub,
                               double* __restrict__ out_rmse, double* __restrict__ out_coef,
                               int32_t* __restrict__ chosen) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     const double yy = *yyp;
+    const int64_t nb = min((int64_t)*bcnt, bcap);
     for (int64_t e = 0; e < nb; e++) taken[e] = !(brss[e] >= 0.0);
     for (int q = 0; q < m; q++) {
         double rmin = INFINITY;
@@ -540,130 +591,113 @@ static void prep_gram(discover_ctx* ctx, const discover_l0_problem& pb, L0Plan& 
     check_launch("k_gram");
 }
 
+// D = 3 blocks (a, 256 consecutive c), ordered so that block p runs on XCD
+// p mod 8 and every XCD sees only the c-groups g with g mod 8 == its index:
+// each XCD's L2 then holds 1/8 of the Gram columns.  Within an XCD queue the
+// heaviest blocks (most b iterations) go first.
+static std::vector<int2> sweep3_blocks(int S) {
+    std::vector<std::vector<std::pair<int64_t, int2>>> q(8);
+    for (int a = 0; a < S - 2; a++)
+        for (int c0 = ((a + 2) / 256) * 256; c0 < S; c0 += 256) {
+            const int cl = std::max(c0, a + 2), ch = std::min(S, c0 + 256);
+            if (cl >= ch) continue;
+            const int64_t work = (int64_t)(ch - 1 - a);
+            q[(c0 / 256) % 8].push_back({work, make_int2(a, c0)});
+        }
+    size_t mx = 0;
+    for (auto& v : q) {
+        std::stable_sort(v.begin(), v.end(), [](const std::pair<int64_t, int2>& x,
+                                                const std::pair<int64_t, int2>& y) {
+            return x.first > y.first;
+        });
+        mx = std::max(mx, v.size());
+    }
+    std::vector<int2> out;
+    out.reserve(mx * 8);
+    for (size_t i = 0; i < mx; i++)
+        for (int x = 0; x < 8; x++) out.push_back(i < q[x].size() ? q[x][i].second : make_int2(-1, 0));
+    return out;
+}
+
 static void l0_problem(discover_ctx* ctx, const discover_l0_problem& pb, int D, int m,
                        int32_t* out_sub, double* out_rmse, double* out_coef, double* out_resid,
                        int64_t ldr, discover_l0_stats& stats, hipStream_t st) {
     L0Plan L;
     prep_gram(ctx, pb, L, st);
     const int S = pb.S;
-    // work items
     std::vector<int2> items;
+    int per = 64;
     if (D == 1) {
         for (int a0 = 0; a0 < S; a0 += 64) items.push_back(make_int2(0, a0));
     } else if (D == 2) {
         for (int a = 0; a < S - 1; a++)
             for (int b0 = a + 1; b0 < S; b0 += 64) items.push_back(make_int2(a, b0));
     } else {
-        // groups of 4 items per a so that a workgroup shares its b-table;
-        // heaviest a first (work ~ (S - a))
-        for (int a = 0; a < S - 2; a++) {
-            int cnt = 0;
-            for (int c0 = a + 2; c0 < S; c0 += 64, cnt++) items.push_back(make_int2(a, c0));
-            while (cnt % 4) { items.push_back(make_int2(a, S)); cnt++; }   // empty pad items
-        }
+        items = sweep3_blocks(S);
+        per = 256;
     }
     const int64_t ni = (int64_t)items.size();
+    const int64_t nl = ni * per;
     int2* d_items = ctx->buf<int2>("l0items", ni);
     DSC_HIP(hipMemcpyAsync(d_items, items.data(), ni * sizeof(int2), hipMemcpyHostToDevice, st));
     SweepArgs g{};
     g.G = L.G; g.ldg = L.ldg; g.S = S; g.D = D; g.items = d_items; g.n_items = ni;
-    g.wbest = ctx->buf<double>("l0wbest", ni);
-    g.wlane = ctx->buf<int32_t>("l0wlane", ni);
-    const unsigned blocks = (unsigned)cdiv(ni, 4);
+    g.lane_q = ctx->buf<double>("l0laneq", nl);
     {
         KTimer kt(ctx, st, D == 3 ? "l0_sweep3" : "l0_sweep");
-        if (D == 1) k_sweep1<false><<<blocks, 256, 0, st>>>(g);
-        else if (D == 2) k_sweep2<false><<<blocks, 256, 0, st>>>(g);
-        else k_sweep3<false><<<blocks, 256, 0, st>>>(g);
+        if (D == 1) k_sweep1<<<(unsigned)cdiv(ni, 4), 256, 0, st>>>(g);
+        else if (D == 2) k_sweep2<<<(unsigned)cdiv(ni, 4), 256, 0, st>>>(g);
+        else k_sweep3<<<(unsigned)ni, 256, 0, st>>>(g);
         check_launch("k_sweep");
     }
-    // threshold from the m-th largest wave best
     uint32_t* hist = ctx->buf<uint32_t>("l0hist", 4096);
     uint32_t* sel = ctx->buf<uint32_t>("l0sel", 4);
     int64_t* sst = ctx->buf<int64_t>("l0selst", 2);
-    radix_select(g.wbest, ni, m, hist, sel, sst, st);
-    std::vector<double> wb(ni);
-    uint32_t hsel[4];
-    int64_t hst[2];
-    DSC_HIP(hipMemcpyAsync(wb.data(), g.wbest, ni * 8, hipMemcpyDeviceToHost, st));
-    DSC_HIP(hipMemcpyAsync(hsel, sel, 16, hipMemcpyDeviceToHost, st));
-    DSC_HIP(hipMemcpyAsync(hst, sst, 16, hipMemcpyDeviceToHost, st));
-    DSC_HIP(hipStreamSynchronize(st));
-    double thr;
-    if (hst[1]) {                        // fewer than m valid waves: collect every valid subset
-        bool any = false;
-        for (double v : wb) any |= v > -0.5;
-        if (!any) DSC_FAIL(DISCOVER_E_NUMERIC, "no non-singular %d-subset", D);
-        thr = -0.5;
-    } else {
-        uint64_t key = ((uint64_t)hsel[0] << 51) | ((uint64_t)hsel[1] << 39) | ((uint64_t)hsel[2] << 27);
-        double th;
-        std::memcpy(&th, &key, 8);
-        thr = th * (1.0 - 1e-12) - GRAM_DELTA;   // slack for the packed low mantissa bits
-    }
-    // waves to sweep again: best >= thr
-    std::vector<int2> again;
-    for (int64_t i = 0; i < ni; i++)
-        if (wb[i] >= thr - 1e-9 && wb[i] > -0.5) again.push_back(items[i]);
-    // keep D = 3 groups of 4 sharing a: re-pad per a
-    if (D == 3) {
-        std::vector<int2> grp;
-        for (size_t i = 0; i < again.size();) {
-            size_t j = i;
-            while (j < again.size() && again[j].x == again[i].x) j++;
-            for (size_t q = i; q < j; q++) grp.push_back(again[q]);
-            while (grp.size() % 4) grp.push_back(make_int2(again[i].x, S));
-            i = j;
-        }
-        again.swap(grp);
-    }
-    int64_t cap = std::max<int64_t>(4096, 64 * (int64_t)again.size());
-    int64_t nb = 0;
+    BandArgs bg{};
+    bg.G = L.G; bg.ldg = L.ldg; bg.S = S; bg.D = D; bg.items = d_items; bg.n_lanes = nl;
+    bg.lane_q = g.lane_q; bg.sel = sel; bg.st = sst;
+    bg.bcnt = ctx->buf<unsigned long long>("l0bcnt", 2);
+    bg.pcnt = bg.bcnt + 1;
+    int64_t cap = std::max<int64_t>(1 << 16, 256 * (int64_t)m);
     for (;;) {
-        g.items = ctx->buf<int2>("l0again", again.size());
-        DSC_HIP(hipMemcpyAsync((void*)g.items, again.data(), again.size() * sizeof(int2),
-                               hipMemcpyHostToDevice, st));
-        g.n_items = (int64_t)again.size();
-        g.thr = thr;
-        g.band = ctx->buf<int4>("l0band", cap);
-        g.bq = ctx->buf<double>("l0bq", cap);
-        g.bcnt = ctx->buf<unsigned long long>("l0bcnt", 1);
-        g.bcap = cap;
-        DSC_HIP(hipMemsetAsync(g.bcnt, 0, 8, st));
-        const unsigned b2 = (unsigned)cdiv(g.n_items, 4);
+        bg.bcap = cap;
+        bg.pcap = cap;
+        bg.band = ctx->buf<int4>("l0band", cap);
+        bg.pairs = ctx->buf<int2>("l0pairs", cap);
+        DSC_HIP(hipMemsetAsync(bg.bcnt, 0, 16, st));
         {
             KTimer kt(ctx, st, "l0_band");
-            if (b2) {
-                if (D == 1) k_sweep1<true><<<b2, 256, 0, st>>>(g);
-                else if (D == 2) k_sweep2<true><<<b2, 256, 0, st>>>(g);
-                else k_sweep3<true><<<b2, 256, 0, st>>>(g);
-            }
-            check_launch("k_sweep(band)");
+            radix_select(g.lane_q, nl, m, hist, sel, sst, st);
+            k_band_lanes<<<(unsigned)std::min<int64_t>(1024, cdiv(nl, 256)), 256, 0, st>>>(bg);
+            if (D == 3) k_band_expand3<<<256, 256, 0, st>>>(bg);
+            check_launch("k_band");
         }
-        unsigned long long c = 0;
-        DSC_HIP(hipMemcpyAsync(&c, g.bcnt, 8, hipMemcpyDeviceToHost, st));
+        // refit every band subset by QR (persistent blocks over the device count)
+        const int nblk = 512;
+        double* scratch = ctx->buf<double>("l0scratch", (size_t)nblk * (D + 2) * pb.n);
+        double* brss = ctx->buf<double>("l0brss", cap);
+        double* bcoef = ctx->buf<double>("l0bcoef", cap * (D + 1));
+        {
+            KTimer kt(ctx, st, "l0_refit");
+            k_refit<<<nblk, 256, 0, st>>>(pb.n, D, pb.F, pb.ldf, pb.y, bg.band, bg.bcnt, cap, scratch,
+                                          brss, bcoef);
+            check_launch("k_refit");
+        }
+        uint8_t* taken = ctx->buf<uint8_t>("l0taken", cap);
+        int32_t* chosen = ctx->buf<int32_t>("l0chosen", m);
+        k_rank_models<<<1, 64, 0, st>>>(bg.band, brss, bcoef, bg.bcnt, cap, D, m, pb.ids, L.yy, pb.n,
+                                        taken, out_sub, out_rmse, out_coef, chosen);
+        check_launch("k_rank_models");
+        unsigned long long cnt[2];
+        DSC_HIP(hipMemcpyAsync(cnt, bg.bcnt, 16, hipMemcpyDeviceToHost, st));
         DSC_HIP(hipStreamSynchronize(st));
-        nb = (int64_t)c;
-        if (nb <= cap) break;
-        cap = nb;
+        if ((int64_t)cnt[0] <= cap && (int64_t)cnt[1] <= cap) {
+            stats.n_band = (int64_t)cnt[0];
+            if (cnt[0] == 0) DSC_FAIL(DISCOVER_E_NUMERIC, "no non-singular %d-subset", D);
+            break;
+        }
+        cap = (int64_t)std::max(cnt[0], cnt[1]) + 1024;
     }
-    stats.n_band = nb;
-    if (nb == 0) DSC_FAIL(DISCOVER_E_NUMERIC, "no non-singular %d-subset", D);
-    // refit the band by QR
-    const int nblk = (int)std::min<int64_t>(nb, 1024);
-    double* scratch = ctx->buf<double>("l0scratch", (size_t)nblk * (D + 2) * pb.n);
-    double* brss = ctx->buf<double>("l0brss", nb);
-    double* bcoef = ctx->buf<double>("l0bcoef", nb * (D + 1));
-    {
-        KTimer kt(ctx, st, "l0_refit");
-        k_refit<<<nblk, 256, 0, st>>>(pb.n, D, pb.F, pb.ldf, pb.y, g.band, nb, scratch, brss, bcoef);
-        check_launch("k_refit");
-    }
-    uint8_t* taken = ctx->buf<uint8_t>("l0taken", nb);
-    int32_t* chosen = ctx->buf<int32_t>("l0chosen", m);
-    k_rank_models<<<1, 64, 0, st>>>(g.band, brss, bcoef, nb, D, m, pb.ids, L.yy, pb.n, taken,
-                                    out_sub, out_rmse, out_coef, chosen);
-    check_launch("k_rank_models");
     if (out_resid) {
         k_resid<<<m, 256, 0, st>>>(pb.n, D, pb.F, pb.ldf, pb.y, out_sub, out_coef, out_resid, ldr);
         check_launch("k_resid");

@@ -22,6 +22,8 @@
 #include "dsc_select.h"
 #include "dsc_space.h"
 
+#include <memory>
+
 namespace dsc {
 
 constexpr double TAU_CONST = 1e-8;   // std <= TAU_CONST * rms  => constant
@@ -320,12 +322,21 @@ struct PairArgs {
     int64_t fix_cap;
 };
 
+// One block = one tile; its 4 waves take consecutive quarters of the samples
+// and their partial moments are summed in LDS in a fixed order (wave 0 +
+// wave 1 + wave 2 + wave 3), so results do not depend on scheduling.
+constexpr int PAIR_SPLIT = 4;
+
 template <int OPS, int J, int TP, bool LIST>
 __global__ __launch_bounds__(256) void k_screen_pairs(PairArgs g) {
     constexpr int NOP = ((OPS >> 0) & 1) + ((OPS >> 1) & 1) + ((OPS >> 2) & 1) +
                         ((OPS >> 3) & 1) + ((OPS >> 4) & 1);
-    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    constexpr int NV = J * NOP * (2 + TP);       // accumulators per lane
+    constexpr int SL = 8;                        // accumulators combined per LDS round
+    __shared__ double red[PAIR_SPLIT - 1][SL][64];
+    const int64_t w = blockIdx.x;
     if (w >= g.n_tiles) return;
+    const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const int2 tile = g.tiles[w];
     const int jc0 = tile.x;
@@ -358,21 +369,19 @@ __global__ __launch_bounds__(256) void k_screen_pairs(PairArgs g) {
         if (OPS & 8) sh[jj][k++] = mua * murb;         // div  = a * (1/b)
         if (OPS & 16) sh[jj][k++] = mura * mub;        // rdiv = b * (1/a)
     }
-    double s1[J][NOP], s2[J][NOP], dt[J][NOP][TP];
+    double acc[NV];
 #pragma unroll
-    for (int jj = 0; jj < J; jj++)
-#pragma unroll
-        for (int k = 0; k < NOP; k++) {
-            s1[jj][k] = 0.0;
-            s2[jj][k] = 0.0;
-#pragma unroll
-            for (int t = 0; t < TP; t++) dt[jj][k][t] = 0.0;
-        }
+    for (int v = 0; v < NV; v++) acc[v] = 0.0;
+#define S1(jj, q) acc[((jj) * NOP + (q)) * (2 + TP)]
+#define S2(jj, q) acc[((jj) * NOP + (q)) * (2 + TP) + 1]
+#define DT(jj, q, t) acc[((jj) * NOP + (q)) * (2 + TP) + 2 + (t)]
 
     const double* __restrict__ Vs = g.Vs;
     const double* __restrict__ Rs = g.Rs;
     const double* __restrict__ Cs = g.Cs;
-    for (int s = 0; s < g.n; s++) {
+    const int chunk = (g.n + PAIR_SPLIT - 1) / PAIR_SPLIT;
+    const int s_lo = min(g.n, wave * chunk), s_hi = min(g.n, s_lo + chunk);
+    for (int s = s_lo; s < s_hi; s++) {
         const int64_t so = (int64_t)s * g.ldm + ic;
         const double a = (OPS & 28) ? Vs[so] : 0.0;
         const double ra = (OPS & 16) ? Rs[so] : 0.0;
@@ -395,13 +404,31 @@ __global__ __launch_bounds__(256) void k_screen_pairs(PairArgs g) {
             if (OPS & 16) { f[k] = fma(ra, b, -sh[jj][k]); k++; }
 #pragma unroll
             for (int q = 0; q < NOP; q++) {
-                s1[jj][q] += f[q];
-                s2[jj][q] = fma(f[q], f[q], s2[jj][q]);
+                S1(jj, q) += f[q];
+                S2(jj, q) = fma(f[q], f[q], S2(jj, q));
 #pragma unroll
-                for (int t = 0; t < TP; t++) dt[jj][q][t] = fma(f[q], y[t], dt[jj][q][t]);
+                for (int t = 0; t < TP; t++) DT(jj, q, t) = fma(f[q], y[t], DT(jj, q, t));
             }
         }
     }
+    // combine the partial moments of the 4 waves into wave 0
+#pragma unroll
+    for (int v0 = 0; v0 < NV; v0 += SL) {
+        if (wave > 0) {
+#pragma unroll
+            for (int v = 0; v < SL; v++)
+                if (v0 + v < NV) red[wave - 1][v][lane] = acc[v0 + v];
+        }
+        __syncthreads();
+        if (wave == 0) {
+#pragma unroll
+            for (int v = 0; v < SL; v++)
+                if (v0 + v < NV)
+                    acc[v0 + v] = ((acc[v0 + v] + red[0][v][lane]) + red[1][v][lane]) + red[2][v][lane];
+        }
+        __syncthreads();
+    }
+    if (wave != 0) return;
 
     const double nn = (double)g.n;
     const int64_t ria = g.mat_raw[ic];
@@ -420,15 +447,15 @@ __global__ __launch_bounds__(256) void k_screen_pairs(PairArgs g) {
                 continue;
             const int64_t id = pair_id(g.sd, g.r, OP_ADD + o, ria, rjb);
             double out[TP];
-            const double S1 = s1[jj][q], S2 = s2[jj][q];
-            const double m1 = S1 / nn;
-            const double varn = S2 - S1 * m1;
+            const double S1v = S1(jj, q), S2v = S2(jj, q);
+            const double m1 = S1v / nn;
+            const double varn = S2v - S1v * m1;
             const double nanv = __longlong_as_double(-1LL);
-            if (!pair_ok || !(S2 < INFINITY) || !(fabs(S1) < INFINITY)) {   // invalid operand or non-finite value
+            if (!pair_ok || !(S2v < INFINITY) || !(fabs(S1v) < INFINITY)) {   // invalid operand or non-finite value
                 for (int t = 0; t < (g.mode ? 1 : g.T); t++) g.scores[(int64_t)t * g.N + id] = nanv;
                 continue;
             }
-            const double kappa = varn > 0.0 ? S2 / varn : INFINITY;
+            const double kappa = varn > 0.0 ? S2v / varn : INFINITY;
             if (!(kappa <= KAPPA_MAX)) {
                 // the shift was far from the mean: decide exactly in the fix-up pass
                 const unsigned long long slot = atomicAdd(g.fix_cnt, 1ull);
@@ -451,7 +478,7 @@ __global__ __launch_bounds__(256) void k_screen_pairs(PairArgs g) {
             double best = 0.0;
 #pragma unroll
             for (int t = 0; t < TP; t++) {
-                out[t] = fabs((dt[jj][q][t] - S1 * g.ysum[t] / nn) * isd);
+                out[t] = fabs((DT(jj, q, t) - S1v * g.ysum[t] / nn) * isd);
                 if (t < g.T) best = fmax(best, out[t]);
             }
             const double err = 4.0 * nn * EPS64 * kappa;
@@ -473,6 +500,9 @@ __global__ __launch_bounds__(256) void k_screen_pairs(PairArgs g) {
     for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor((int)cnt, o, 64);
     tot = cnt;
     if (lane == 0 && tot) atomicAdd(g.nscored, tot);
+#undef S1
+#undef S2
+#undef DT
 }
 
 // ------------------------------------------------------------ selection
@@ -497,7 +527,8 @@ __global__ __launch_bounds__(256) void k_compact(const double* __restrict__ sc, 
 // Exact FP64 rescore of the pool (one wave per entry); also flags entries
 // whose ID is excluded.
 template <int TMAX>
-__global__ __launch_bounds__(256) void k_rescore(const int64_t* __restrict__ pool, int64_t P,
+__global__ __launch_bounds__(256) void k_rescore(const int64_t* __restrict__ pool,
+                                                 const unsigned long long* __restrict__ Pp, int64_t cap,
                                                  SpaceDev sd, int streamed,
                                                  const int32_t* __restrict__ raw2c,
                                                  const uint8_t* __restrict__ valid, Ops o, int n,
@@ -507,9 +538,9 @@ __global__ __launch_bounds__(256) void k_rescore(const int64_t* __restrict__ poo
                                                  const int64_t* __restrict__ excl, int n_excl,
                                                  double* __restrict__ ps,
                                                  uint8_t* __restrict__ pex) {
-    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (w >= P) return;
+    const int64_t P = min((int64_t)*Pp, cap);
     const int lane = threadIdx.x & 63;
+    for (int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); w < P; w += (int64_t)gridDim.x * 4) {
     const int64_t id = pool[w];
     Cand c;
     bool ok = cand_of_id(sd, streamed, raw2c, id, c);
@@ -533,6 +564,7 @@ __global__ __launch_bounds__(256) void k_rescore(const int64_t* __restrict__ poo
         ps[w] = s;
         pex[w] = (uint8_t)ex;
     }
+    }
 }
 
 // Exact two-pass score of the candidates whose shifted one-pass moments
@@ -547,30 +579,33 @@ __global__ __launch_bounds__(256) void k_fixup(const int64_t* __restrict__ ids,
                                                const double* __restrict__ syy, int64_t N,
                                                double* __restrict__ scores,
                                                unsigned long long* __restrict__ nscored) {
-    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int64_t m = min((int64_t)*cnt, cap);
-    if (w >= m) return;
-    const int64_t id = ids[w];
-    Cand c;
-    bool ok = cand_of_id(sd, streamed, raw2c, id, c);
-    ok = ok && valid[c.ca] && (c.kind < 2 || valid[c.cb]);
-    double r[TMAX];
-    ok = ok && wave_exact_r<TMAX>(c, o, n, T, Yc, syy, r);
-    if ((threadIdx.x & 63) != 0 || !ok) return;
-    atomicAdd(nscored, 1ull);
-    if (mode == DISCOVER_SCORE_MAX) {
-        double mx = 0.0;
-        for (int t = 0; t < T; t++) mx = fmax(mx, fabs(r[t]));
-        scores[id] = mx;
-    } else {
-        for (int t = 0; t < T; t++) scores[(int64_t)t * N + id] = fabs(r[t]);
+    for (int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); w < m; w += (int64_t)gridDim.x * 4) {
+        const int64_t id = ids[w];
+        Cand c;
+        bool ok = cand_of_id(sd, streamed, raw2c, id, c);
+        ok = ok && valid[c.ca] && (c.kind < 2 || valid[c.cb]);
+        double r[TMAX];
+        ok = ok && wave_exact_r<TMAX>(c, o, n, T, Yc, syy, r);
+        if ((threadIdx.x & 63) != 0 || !ok) continue;
+        atomicAdd(nscored, 1ull);
+        if (mode == DISCOVER_SCORE_MAX) {
+            double mx = 0.0;
+            for (int t = 0; t < T; t++) mx = fmax(mx, fabs(r[t]));
+            scores[id] = mx;
+        } else {
+            for (int t = 0; t < T; t++) scores[(int64_t)t * N + id] = fabs(r[t]);
+        }
     }
 }
 
 // Rank sort of the pool by (-score, ID).
 __global__ __launch_bounds__(256) void k_rank(const double* __restrict__ ps,
-                                              const int64_t* __restrict__ pool, int64_t P,
+                                              const int64_t* __restrict__ pool,
+                                              const unsigned long long* __restrict__ Pp, int64_t cap,
                                               int32_t* __restrict__ order) {
+    const int64_t P = min((int64_t)*Pp, cap);
+    if (P <= 4096) return;                      // handled by k_bitonic
     __shared__ double ts[1024];
     __shared__ int64_t ti[1024];
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -593,9 +628,11 @@ __global__ __launch_bounds__(256) void k_rank(const double* __restrict__ ps,
 // Near-tie window of each sorted entry: lo[q] = first earlier position whose
 // score is within TAU_NEAR (relative) of entry q, scanning backwards.
 __global__ void k_window(const double* __restrict__ ps, const int32_t* __restrict__ order,
-                         int64_t P, int32_t* __restrict__ lo, int32_t* __restrict__ cnt) {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= P) return;
+                         const unsigned long long* __restrict__ Pp, int64_t cap,
+                         int32_t* __restrict__ lo, int32_t* __restrict__ cnt) {
+    const int64_t P = min((int64_t)*Pp, cap);
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < P;
+         q += (int64_t)gridDim.x * blockDim.x) {
     const double s = ps[order[q]];
     int64_t l = q;
     if (s > 0.0)
@@ -606,11 +643,14 @@ __global__ void k_window(const double* __restrict__ ps, const int32_t* __restric
         }
     lo[q] = (int32_t)l;
     cnt[q] = (int32_t)(q - l);
+    }
 }
 
 // Exclusive prefix sum of cnt (single block).
-__global__ __launch_bounds__(1024) void k_scan_offsets(const int32_t* __restrict__ cnt, int64_t P,
-                                                       int64_t* __restrict__ off) {
+__global__ __launch_bounds__(1024) void k_scan_offsets(const int32_t* __restrict__ cnt,
+                                                       const unsigned long long* __restrict__ Pp,
+                                                       int64_t cap, int64_t* __restrict__ off) {
+    const int64_t P = min((int64_t)*Pp, cap);
     __shared__ int64_t part[1024];
     const int64_t per = (P + 1023) / 1024;
     const int64_t b = threadIdx.x * per, e = min(P, b + per);
@@ -640,14 +680,16 @@ __global__ __launch_bounds__(1024) void k_scan_offsets(const int32_t* __restrict
 __global__ __launch_bounds__(256) void k_pairs(const int64_t* __restrict__ pool,
                                                const int32_t* __restrict__ order,
                                                const int32_t* __restrict__ lo,
-                                               const int64_t* __restrict__ off, int64_t P,
+                                               const int64_t* __restrict__ off,
+                                               const unsigned long long* __restrict__ Pp, int64_t cap,
                                                SpaceDev sd, int streamed,
                                                const int32_t* __restrict__ raw2c, Ops o, int n,
-                                               uint8_t* __restrict__ flag) {
-    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int64_t total = off[P];
-    if (w >= total) return;
+                                               uint8_t* __restrict__ flag, int64_t flag_cap) {
+    const int64_t P = min((int64_t)*Pp, cap);
+    const int64_t total = min(off[P], flag_cap);
     const int lane = threadIdx.x & 63;
+    for (int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); w < total;
+         w += (int64_t)gridDim.x * 4) {
     // find q with off[q] <= w < off[q+1]
     int64_t a = 0, b = P;
     while (b - a > 1) {
@@ -661,7 +703,7 @@ __global__ __launch_bounds__(256) void k_pairs(const int64_t* __restrict__ pool,
                      cand_of_id(sd, streamed, raw2c, pool[order[q]], cv);
     if (!okp) {
         if (lane == 0) flag[w] = 0;
-        return;
+        continue;
     }
     double su = 0.0, sv = 0.0;
     for (int i = lane; i < n; i += 64) {
@@ -680,90 +722,195 @@ __global__ __launch_bounds__(256) void k_pairs(const int64_t* __restrict__ pool,
     vv = wave_sum(vv);
     uv = wave_sum(uv);
     if (lane == 0) flag[w] = fabs(uv) / sqrt(uu * vv) >= 1.0 - TAU_DUP;
+    }
 }
 
-// Group scan (one thread): forms duplicate groups in sorted order, blocks
-// groups that contain an excluded ID, stops once the k-th unblocked group's
-// near-tie window has closed.  res: [0] selected, [1] complete, [2] merged.
-__global__ void k_groups(const int64_t* __restrict__ pool, const double* __restrict__ ps,
-                         const uint8_t* __restrict__ pex, const int32_t* __restrict__ order,
-                         const int32_t* __restrict__ lo, const int64_t* __restrict__ off,
-                         const uint8_t* __restrict__ flag, int64_t P, int k, int dedup,
-                         const uint32_t* __restrict__ sel, const int64_t* __restrict__ st,
-                         double margin, int32_t* __restrict__ hpos, uint8_t* __restrict__ hblk,
-                         int64_t* __restrict__ hmin, double* __restrict__ hsc,
-                         int64_t* __restrict__ out_ids, double* __restrict__ out_sc,
-                         int64_t* __restrict__ res) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Duplicate groups of the sorted pool, formed in parallel by one block of
+// 1024 threads.  In sorted order, an entry joins the earliest group head in
+// its near-tie window with which it is flagged a duplicate, otherwise it
+// heads a new group (decided in rounds: an entry is decided once every
+// flagged entry before it is).  Groups holding an excluded ID are blocked;
+// each group is represented by its smallest ID; the first k unblocked
+// groups in head order are returned in (-score, ID) order.  The result is
+// complete when the pool reaches below the near-tie window of the k-th
+// unblocked head, or when the pool holds every candidate.
+// res: [0] selected, [1] complete, [2] merged duplicates.
+constexpr int GRP_THREADS = 1024;
+
+__device__ __forceinline__ int64_t block_excl_scan(int64_t v, int64_t* part) {
+    const int t = threadIdx.x;
+    part[t] = v;
+    __syncthreads();
+    for (int o = 1; o < GRP_THREADS; o <<= 1) {
+        const int64_t x = t >= o ? part[t - o] : 0;
+        __syncthreads();
+        part[t] += x;
+        __syncthreads();
+    }
+    const int64_t incl = part[t];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ __launch_bounds__(GRP_THREADS) void k_groups(
+    const int64_t* __restrict__ pool, const double* __restrict__ ps, const uint8_t* __restrict__ pex,
+    const int32_t* __restrict__ order, const int32_t* __restrict__ lo, const int64_t* __restrict__ off,
+    const uint8_t* __restrict__ flag, const unsigned long long* __restrict__ Pp, int64_t cap,
+    int64_t flag_cap, int k, int dedup, const uint32_t* __restrict__ sel,
+    const int64_t* __restrict__ st, double margin, int32_t* __restrict__ parent,
+    int32_t* __restrict__ blk, unsigned long long* __restrict__ repid, int32_t* __restrict__ reppos,
+    int32_t* __restrict__ headpos, int64_t* __restrict__ out_ids, double* __restrict__ out_sc,
+    int64_t* __restrict__ res) {
+    __shared__ int64_t part[GRP_THREADS];
+    __shared__ int changed, undecided;
+    const int64_t P = min((int64_t)*Pp, cap);
+    const int t = threadIdx.x;
     const bool all = st[1] != 0;
     const double th_scan = all ? -1.0 : select_threshold(sel, st) - margin;
-    int64_t nh = 0, nunb = 0, kth = -1, merged = 0;
-    bool stopped = false, short_pool = false;
-    double lim = 0.0;
-    int64_t q = 0;
-    for (; q < P; q++) {
-        const int32_t e = order[q];
-        const double s = ps[e];
-        if (!(s > 0.0)) { q = P; break; }              // past the last valid entry
-        if (kth >= 0 && s < (1.0 - TAU_NEAR) * lim) { stopped = true; break; }
-        if (s < th_scan) { short_pool = true; break; }
-        const int64_t id = pool[e];
-        int64_t grp = -1;
-        if (dedup) {
-            for (int64_t h = nh - 1; h >= 0 && hpos[h] >= lo[q]; h--)
-                if (flag[off[q] + (hpos[h] - lo[q])]) grp = h;
+    volatile int32_t* vpar = parent;
+    // 1. initial decisions
+    for (int64_t q = t; q < P; q += GRP_THREADS) {
+        const double sq = ps[order[q]];
+        int32_t v = (int32_t)q;
+        if (!(sq > 0.0)) v = -3;                           // invalid after exact rescoring
+        else if (dedup) {
+            for (int64_t p2 = lo[q]; p2 < q; p2++)
+                if (off[q] + (p2 - lo[q]) < flag_cap && flag[off[q] + (p2 - lo[q])]) { v = -2; break; }
         }
-        if (grp < 0) {
-            hpos[nh] = (int32_t)q;
-            hblk[nh] = pex[e];
-            hmin[nh] = id;
-            hsc[nh] = s;
-            if (!pex[e]) {
-                nunb++;
-                if (nunb == k) { kth = nh; lim = s; }
+        parent[q] = v;
+        blk[q] = 0;
+        repid[q] = ~0ull;
+        reppos[q] = -1;
+    }
+    __syncthreads();
+    // 2. rounds
+    for (;;) {
+        if (t == 0) { changed = 0; undecided = 0; }
+        __syncthreads();
+        for (int64_t q = t; q < P; q += GRP_THREADS) {
+            if (vpar[q] != -2) continue;
+            int32_t dec = (int32_t)q;                       // head unless a flagged head comes first
+            bool wait = false;
+            for (int64_t p2 = lo[q]; p2 < q; p2++) {
+                if (off[q] + (p2 - lo[q]) >= flag_cap || !flag[off[q] + (p2 - lo[q])]) continue;
+                const int32_t sp2 = vpar[p2];
+                if (sp2 == -2) { wait = true; break; }
+                if (sp2 == (int32_t)p2) { dec = (int32_t)p2; break; }
             }
-            nh++;
-        } else {
-            merged++;
-            if (id < hmin[grp]) { hmin[grp] = id; hsc[grp] = s; }
-            if (pex[e] && !hblk[grp]) {
-                hblk[grp] = 1;
-                nunb--;
-                if (kth >= 0 && grp <= kth) {
-                    int64_t h = kth + 1;
-                    while (h < nh && hblk[h]) h++;
-                    if (h < nh) { kth = h; lim = ps[order[hpos[h]]]; }
-                    else { kth = -1; }
+            if (wait) { atomicAdd(&undecided, 1); continue; }
+            vpar[q] = dec;
+            atomicAdd(&changed, 1);
+        }
+        __syncthreads();
+        const int ch = changed, un = undecided;
+        __syncthreads();
+        if (un == 0 || ch == 0) break;
+    }
+    // 3. aggregate groups onto their heads
+    int64_t merged_loc = 0;
+    for (int64_t q = t; q < P; q += GRP_THREADS) {
+        const int32_t h = vpar[q];
+        if (h < 0) continue;
+        const int e = order[q];
+        if (pex[e]) atomicOr(&blk[h], 1);
+        atomicMin(&repid[h], (unsigned long long)pool[e]);
+        merged_loc += h != (int32_t)q;
+    }
+    __syncthreads();
+    for (int64_t q = t; q < P; q += GRP_THREADS) {
+        const int32_t h = vpar[q];
+        if (h >= 0 && (unsigned long long)pool[order[q]] == repid[h]) reppos[h] = (int32_t)q;
+    }
+    __syncthreads();
+    // 4. rank the unblocked heads in sorted order (chunked block scan)
+    const int64_t chunk = (P + GRP_THREADS - 1) / GRP_THREADS;
+    const int64_t q0 = t * chunk, q1 = min(P, q0 + chunk);
+    int64_t cnt = 0;
+    for (int64_t q = q0; q < q1; q++) cnt += (vpar[q] == (int32_t)q && !blk[q]);
+    int64_t r = block_excl_scan(cnt, part);
+    const int64_t nunb = part[GRP_THREADS - 1];
+    for (int64_t q = q0; q < q1; q++)
+        if (vpar[q] == (int32_t)q && !blk[q]) {
+            if (r < k) headpos[r] = (int32_t)q;
+            r++;
+        }
+    const int64_t merged = block_excl_scan(merged_loc, part) + merged_loc;
+    const int64_t merged_tot = part[GRP_THREADS - 1];
+    (void)merged;
+    __syncthreads();
+    const int64_t ns = min((int64_t)k, nunb);
+    // 5. representatives in (-score, ID) order (rank sort of <= k entries)
+    for (int64_t i = t; i < ns; i += GRP_THREADS) {
+        const int32_t rp = reppos[headpos[i]];
+        const double si = ps[order[rp]];
+        const int64_t ii = pool[order[rp]];
+        int64_t rank = 0;
+        for (int64_t j = 0; j < ns; j++) {
+            const int32_t rq = reppos[headpos[j]];
+            const double sj = ps[order[rq]];
+            const int64_t ij = pool[order[rq]];
+            rank += (sj > si) || (sj == si && ij < ii);
+        }
+        out_ids[rank] = ii;
+        out_sc[rank] = si;
+    }
+    for (int64_t i = ns + t; i < k; i += GRP_THREADS) {
+        out_ids[i] = -1;
+        out_sc[i] = __longlong_as_double(0x7FF8000000000000LL);
+    }
+    if (t == 0) {
+        bool complete = all;
+        if (!all && nunb >= k) {
+            const double lim = ps[order[headpos[k - 1]]];
+            complete = (1.0 - TAU_NEAR) * lim >= th_scan;
+        }
+        res[0] = ns;
+        res[1] = complete ? 1 : 0;
+        res[2] = merged_tot;
+        res[3] = P > 0 ? off[P] : 0;            // duplicate-check pairs (capacity check)
+        res[4] = (int64_t)*Pp;                  // pool size (capacity check)
+    }
+}
+
+// Sort of a pool of at most 4096 entries by (-score, ID): bitonic network
+// in LDS, one block of 1024 threads.
+constexpr int BITONIC_MAX = 4096;
+
+__global__ __launch_bounds__(1024) void k_bitonic(const double* __restrict__ ps,
+                                                  const int64_t* __restrict__ pool,
+                                                  const unsigned long long* __restrict__ Pp,
+                                                  int64_t cap, int32_t* __restrict__ order) {
+    const int64_t P = min((int64_t)*Pp, cap);
+    if (P > BITONIC_MAX) return;                // handled by k_rank
+    __shared__ double ks[BITONIC_MAX];
+    __shared__ int64_t ki[BITONIC_MAX];
+    __shared__ int32_t kx[BITONIC_MAX];
+    int N2 = 1;
+    while (N2 < P) N2 <<= 1;
+    for (int i = threadIdx.x; i < N2; i += 1024) {
+        ks[i] = i < P ? ps[i] : -INFINITY;
+        ki[i] = i < P ? pool[i] : INT64_MAX;
+        kx[i] = i;
+    }
+    __syncthreads();
+    for (int size = 2; size <= N2; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int u = threadIdx.x; u < N2 / 2; u += 1024) {
+                const int i = 2 * stride * (u / stride) + (u % stride);
+                const int j = i + stride;
+                const bool up = (i & size) == 0;
+                // "before(a, b)": a.s > b.s, ties by smaller ID
+                const bool jb = ks[j] > ks[i] || (ks[j] == ks[i] && ki[j] < ki[i]);
+                if (jb == up) {
+                    const double ts = ks[i]; ks[i] = ks[j]; ks[j] = ts;
+                    const int64_t ti = ki[i]; ki[i] = ki[j]; ki[j] = ti;
+                    const int32_t tx = kx[i]; kx[i] = kx[j]; kx[j] = tx;
                 }
             }
+            __syncthreads();
         }
     }
-    bool complete;
-    if (stopped) complete = true;
-    else if (short_pool) complete = false;
-    else complete = all || (kth >= 0 && (1.0 - TAU_NEAR) * lim >= th_scan);   // pool exhausted
-    // representatives of the first k unblocked groups, then (-score, ID) order
-    int64_t ns = 0;
-    for (int64_t h = 0; h < nh && ns < k; h++) {
-        if (hblk[h]) continue;
-        int64_t j = ns++;
-        const double s = hsc[h];
-        const int64_t id = hmin[h];
-        while (j > 0 && (out_sc[j - 1] < s || (out_sc[j - 1] == s && out_ids[j - 1] > id))) {
-            out_sc[j] = out_sc[j - 1];
-            out_ids[j] = out_ids[j - 1];
-            j--;
-        }
-        out_sc[j] = s;
-        out_ids[j] = id;
-    }
-    for (int64_t j = ns; j < k; j++) {
-        out_ids[j] = -1;
-        out_sc[j] = __longlong_as_double(0x7FF8000000000000LL);
-    }
-    res[0] = ns;
-    res[1] = complete ? 1 : 0;
-    res[2] = merged;
+    for (int i = threadIdx.x; i < P; i += 1024) order[i] = kx[i];
 }
 
 // Values of the selected candidates: one wave per output row.
@@ -786,12 +933,19 @@ __global__ __launch_bounds__(256) void k_values(const int64_t* __restrict__ ids,
 // ====================================================================== host
 namespace dsc {
 
+template <class T>
+static T download1(const T* src, hipStream_t st) {
+    T v;
+    DSC_HIP(hipMemcpyAsync(&v, src, sizeof(T), hipMemcpyDeviceToHost, st));
+    DSC_HIP(hipStreamSynchronize(st));
+    return v;
+}
+
 static int pad_targets(int T) { return T <= 1 ? 1 : T <= 2 ? 2 : T <= 4 ? 4 : T <= 8 ? 8 : 16; }
 
-// Dense and list pair launches for one op class.
 template <int OPS, int J, int TP>
 static void launch_pairs_t(const PairArgs& a, bool list, hipStream_t st) {
-    const int64_t blocks = cdiv(a.n_tiles, 4);
+    const int64_t blocks = a.n_tiles;          // one 256-thread block per tile
     if (blocks == 0) return;
     if (list) k_screen_pairs<OPS, 1, TP, true><<<(unsigned)blocks, 256, 0, st>>>(a);
     else k_screen_pairs<OPS, J, TP, false><<<(unsigned)blocks, 256, 0, st>>>(a);
@@ -819,98 +973,74 @@ static void launch_pairs(int OPS, const PairArgs& a, bool list, int TP, hipStrea
     }
 }
 
-template <class T>
-static void upload(T* dst, const std::vector<T>& v, hipStream_t st) {
-    if (!v.empty()) DSC_HIP(hipMemcpyAsync(dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
-}
-
-template <class T>
-static T download1(const T* src, hipStream_t st) {
-    T v;
-    DSC_HIP(hipMemcpyAsync(&v, src, sizeof(T), hipMemcpyDeviceToHost, st));
-    DSC_HIP(hipStreamSynchronize(st));
-    return v;
-}
-
-struct Problem {
+// Device-resident description of one search space and its work lists,
+// cached in the context: it depends only on (p, n, units, parameters).
+struct Plan {
     Space sp;
-    int n, T, Tl, TP, ldn, ldm, Mc;
-    double *Vf, *Rf, *Cf, *Vs, *Rs, *Cs, *mu, *mur, *Yc, *Yn, *syy, *ysum, *scores;
-    uint8_t* valid;
-    int32_t* raw2c;
-    int64_t* mat_raw;
-    unsigned long long* nscored;
+    int n = 0, TP = 1, ldn = 0, ldm = 0;
+    std::vector<void*> allocs;
+    int32_t* raw2c = nullptr;
+    int64_t* mat_raw = nullptr;
+    int8_t* mat_op = nullptr;
+    int32_t *mat_a = nullptr, *mat_b = nullptr;
+    ListItem* items = nullptr;
+    int64_t n_items = 0;
+    int2* dtiles = nullptr;
+    int64_t n_dtiles = 0;
+    uint32_t dense_ops = 0;
+    int dense_cls = 0;
+    int2* ltiles = nullptr;
+    int32_t *ilist = nullptr, *icount = nullptr;
+    int64_t n_ltiles = 0;
+    uint32_t list_ops = 0;
+
+    template <class T>
+    T* up(const std::vector<T>& v) {
+        void* p = nullptr;
+        const size_t bytes = std::max<size_t>(v.size() * sizeof(T), 16);
+        if (hipMalloc(&p, bytes) != hipSuccess) DSC_FAIL(DISCOVER_E_NOMEM, "plan allocation failed");
+        allocs.push_back(p);
+        if (!v.empty()) DSC_HIP(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+        return (T*)p;
+    }
+    ~Plan() {
+        for (void* p : allocs)
+            if (hipFree(p) != hipSuccess) { /* nothing to do */ }
+    }
 };
 
-// Enumerate, materialise the operand features, and screen every candidate
-// into the score slots.
-static void screen_problem(discover_ctx* ctx, const discover_problem& pb,
-                           const discover_screen_params& prm, Problem& P, hipStream_t st) {
-    Space& sp = P.sp;
+static std::string plan_key(const discover_problem& pb, const discover_screen_params& prm) {
+    std::string k((const char*)&prm.ops, sizeof prm.ops);
+    k.append((const char*)&prm.rung, sizeof prm.rung);
+    k.append((const char*)prm.rung_ops, sizeof prm.rung_ops);
+    k.append((const char*)prm.rung_pool, sizeof prm.rung_pool);
+    const int32_t dims[4] = {pb.p, pb.n, pb.B, pad_targets(pb.T)};
+    k.append((const char*)dims, sizeof dims);
+    if (pb.B && pb.units) k.append((const char*)pb.units, sizeof(int32_t) * pb.p * pb.B);
+    return k;
+}
+
+static std::shared_ptr<Plan> get_plan(discover_ctx* ctx, const discover_problem& pb,
+                                      const discover_screen_params& prm) {
+    const std::string key = plan_key(pb, prm);
+    auto it = ctx->plans.find(key);
+    if (it != ctx->plans.end()) return std::static_pointer_cast<Plan>(it->second);
+    if (ctx->plans.size() >= 16) ctx->plans.clear();
+    auto P = std::make_shared<Plan>();
+    Space& sp = P->sp;
     build_space(sp, pb.p, prm, pb.B, pb.units);
     const SpaceDev& sd = sp.d;
-    const int n = pb.n;
-    P.n = n;
-    P.T = pb.T;
-    P.Tl = prm.score_mode == DISCOVER_SCORE_MAX ? 1 : pb.T;
-    P.TP = pad_targets(pb.T);
-    P.ldn = (int)((n + 63) / 64 * 64);
-    P.Mc = sp.Mc();
-    P.ldm = (int)((P.Mc + 63) / 64 * 64);
-    const int Mc = P.Mc, ldn = P.ldn, ldm = P.ldm;
-    const int64_t N = sp.n_raw();
-
-    P.Vf = ctx->buf<double>("Vf", (size_t)Mc * ldn);
-    P.Rf = ctx->buf<double>("Rf", (size_t)Mc * ldn);
-    P.Cf = ctx->buf<double>("Cf", (size_t)Mc * ldn);
-    P.mu = ctx->buf<double>("mu", Mc);
-    P.mur = ctx->buf<double>("mur", Mc);
-    P.valid = ctx->buf<uint8_t>("valid", Mc);
-    P.raw2c = ctx->buf<int32_t>("raw2c", sp.M_raw);
-    P.mat_raw = ctx->buf<int64_t>("mat_raw", Mc);
-    int8_t* d_op = ctx->buf<int8_t>("mat_op", Mc);
-    int32_t* d_a = ctx->buf<int32_t>("mat_a", Mc);
-    int32_t* d_b = ctx->buf<int32_t>("mat_b", Mc);
-    upload(P.raw2c, sp.raw2c, st);
-    upload(P.mat_raw, sp.mat_raw, st);
-    upload(d_op, sp.mat_op, st);
-    upload(d_a, sp.mat_a, st);
-    upload(d_b, sp.mat_b, st);
-
-    // targets
-    P.Yc = ctx->buf<double>("Yc", (size_t)pb.T * ldn);
-    P.Yn = ctx->buf<double>("Yn", (size_t)P.TP * ldn);
-    P.syy = ctx->buf<double>("syy", pb.T);
-    P.ysum = ctx->buf<double>("ysum", P.TP);
-    int* bad = ctx->buf<int>("bad", 1);
-    DSC_HIP(hipMemsetAsync(P.Yn, 0, (size_t)P.TP * ldn * 8, st));
-    DSC_HIP(hipMemsetAsync(P.ysum, 0, (size_t)P.TP * 8, st));
-    DSC_HIP(hipMemsetAsync(bad, 0, 4, st));
-    k_targets<<<pb.T, 256, 0, st>>>(n, pb.T, pb.Y, pb.ldy, ldn, P.Yc, P.Yn, P.syy, P.ysum, bad);
-    check_launch("k_targets");
-    if (download1(bad, st)) DSC_FAIL(DISCOVER_E_NUMERIC, "a target column is constant or not finite");
-
-    // operand features, rung by rung
-    {
-        KTimer kt(ctx, st, "materialise");
-        for (size_t r = 0; r + 1 < sp.rung_start.size(); r++) {
-            const int c0 = sp.rung_start[r], c1 = sp.rung_start[r + 1];
-            if (c1 <= c0) continue;
-            dim3 g((unsigned)cdiv(n, 256), (unsigned)(c1 - c0));
-            k_mat_values<<<g, 256, 0, st>>>(n, ldn, c0, c1, pb.X, pb.ldx, d_op, d_a, d_b,
-                                            P.mat_raw, P.Vf);
-            k_mat_stats<<<(unsigned)cdiv(c1 - c0, 4), 256, 0, st>>>(n, ldn, c0, c1, d_a, d_b, P.Vf,
-                                                                     P.Rf, P.Cf, P.mu, P.mur, P.valid);
-        }
-        check_launch("k_mat");
-    }
-    P.nscored = ctx->buf<unsigned long long>("nscored", 1);
-    DSC_HIP(hipMemsetAsync(P.nscored, 0, 8, st));
-    P.scores = ctx->buf<double>("scores", (size_t)P.Tl * N);
-    DSC_HIP(hipMemsetAsync(P.scores, 0xFF, (size_t)P.Tl * N * 8, st));
-    Ops ops{P.Vf, P.Rf, ldn};
-
-    // operand features and unary candidates of the streamed rung: exact scores
+    P->n = pb.n;
+    P->TP = pad_targets(pb.T);
+    P->ldn = (int)((pb.n + 63) / 64 * 64);
+    const int Mc = sp.Mc();
+    P->ldm = (int)((Mc + 63) / 64 * 64);
+    P->raw2c = P->up(sp.raw2c);
+    P->mat_raw = P->up(sp.mat_raw);
+    P->mat_op = P->up(sp.mat_op);
+    P->mat_a = P->up(sp.mat_a);
+    P->mat_b = P->up(sp.mat_b);
+    // operand features and unary candidates of the streamed rung: exact list
     std::vector<ListItem> items;
     for (int32_t c = 0; c < Mc; c++) items.push_back({sp.mat_raw[c], 0, OP_NONE, c, -1});
     const int R = sp.streamed;
@@ -925,18 +1055,135 @@ static void screen_problem(discover_ctx* ctx, const discover_problem& pb,
                     items.push_back({unary_id(sd, R, o, sp.mat_raw[c]), 1, o, c, -1});
         }
     }
-    ListItem* d_items = ctx->buf<ListItem>("items", items.size());
-    upload(d_items, items, st);
+    P->items = P->up(items);
+    P->n_items = (int64_t)items.size();
+    if (!R) return ctx->plans[key] = P, P;
+    uint32_t bin = 0;
+    for (int o = OP_ADD; o <= OP_RDIV; o++)
+        if (sd.block[R][o] >= 0) bin |= 1u << (o - OP_ADD);
+    const int32_t jc0 = sp.rung_start[R - 1], jc1 = sp.rung_start[R];
+    const int pool = sd.pool[R];
+    const int32_t i_end = pool == R - 1 ? Mc : sp.rung_start[pool + 1];
+    const bool units = sp.B > 0;
+    P->dense_ops = units ? (bin & 28u) : bin;
+    P->list_ops = units ? (bin & 3u) : 0u;
+    P->dense_cls = units ? 28 : 31;
+    if (P->dense_ops) {
+        const int J = dense_J(P->TP);
+        std::vector<int2> tiles;
+        for (int32_t j = jc0; j < jc1; j += J) {
+            const int32_t ilim = std::min<int32_t>(i_end, std::min<int32_t>(j + J - 1, jc1 - 1));
+            for (int32_t i0 = 0; i0 < ilim; i0 += 64) tiles.push_back(make_int2(j, i0));
+        }
+        P->dtiles = P->up(tiles);
+        P->n_dtiles = (int64_t)tiles.size();
+    }
+    if (P->list_ops) {
+        std::vector<int2> tiles;
+        std::vector<int32_t> il, ic;
+        std::map<std::string, std::vector<int32_t>> by_unit;
+        auto key_of = [&](int32_t c) {
+            return std::string((const char*)&sp.mat_unit[(size_t)c * Bq], sizeof(int32_t) * Bq);
+        };
+        if (pool != R - 1)
+            for (int32_t c = 0; c < i_end; c++) by_unit[key_of(c)].push_back(c);
+        for (int32_t c = 0; c < jc1; c++) {
+            if (c >= jc0) {
+                auto f = by_unit.find(key_of(c));
+                if (f != by_unit.end()) {
+                    const auto& v = f->second;
+                    for (size_t q = 0; q < v.size(); q += 64) {
+                        tiles.push_back(make_int2(c, (int)il.size()));
+                        const int cnt = (int)std::min<size_t>(64, v.size() - q);
+                        ic.push_back(cnt);
+                        il.insert(il.end(), v.begin() + q, v.begin() + q + cnt);
+                    }
+                }
+            }
+            if (pool == R - 1) by_unit[key_of(c)].push_back(c);
+        }
+        P->ltiles = P->up(tiles);
+        P->ilist = P->up(il);
+        P->icount = P->up(ic);
+        P->n_ltiles = (int64_t)tiles.size();
+    }
+    ctx->plans[key] = P;
+    return P;
+}
+
+struct Problem {
+    std::shared_ptr<Plan> plan;
+    int n, T, Tl, TP, ldn, ldm, Mc;
+    double *Vf, *Rf, *Cf, *Vs, *Rs, *Cs, *mu, *mur, *Yc, *Yn, *syy, *ysum, *scores;
+    uint8_t* valid;
+    int* bad;
+    unsigned long long* nscored;
+};
+
+// Materialise the operand features and screen every candidate into the
+// score slots (no host synchronisation).
+static void screen_problem(discover_ctx* ctx, const discover_problem& pb,
+                           const discover_screen_params& prm, Problem& P, hipStream_t st) {
+    P.plan = get_plan(ctx, pb, prm);
+    const Plan& pl = *P.plan;
+    const Space& sp = pl.sp;
+    const SpaceDev& sd = sp.d;
+    const int n = pb.n;
+    P.n = n;
+    P.T = pb.T;
+    P.Tl = prm.score_mode == DISCOVER_SCORE_MAX ? 1 : pb.T;
+    P.TP = pl.TP;
+    P.ldn = pl.ldn;
+    P.ldm = pl.ldm;
+    P.Mc = sp.Mc();
+    const int Mc = P.Mc, ldn = P.ldn, ldm = P.ldm;
+    const int64_t N = sp.n_raw();
+
+    P.Vf = ctx->buf<double>("Vf", (size_t)Mc * ldn);
+    P.Rf = ctx->buf<double>("Rf", (size_t)Mc * ldn);
+    P.Cf = ctx->buf<double>("Cf", (size_t)Mc * ldn);
+    P.mu = ctx->buf<double>("mu", Mc);
+    P.mur = ctx->buf<double>("mur", Mc);
+    P.valid = ctx->buf<uint8_t>("valid", Mc);
+    P.Yc = ctx->buf<double>("Yc", (size_t)pb.T * ldn);
+    P.Yn = ctx->buf<double>("Yn", (size_t)P.TP * ldn);
+    P.syy = ctx->buf<double>("syy", pb.T);
+    P.ysum = ctx->buf<double>("ysum", P.TP);
+    // counters: [0] bad target, [1] fix-up count, [2] scored (as u64 slots)
+    unsigned long long* ctr = ctx->buf<unsigned long long>("screen_ctr", 4);
+    P.bad = (int*)ctr;
+    P.nscored = ctr + 2;
+    unsigned long long* fix_cnt = ctr + 1;
+    DSC_HIP(hipMemsetAsync(ctr, 0, 32, st));
+    DSC_HIP(hipMemsetAsync(P.Yn, 0, (size_t)P.TP * ldn * 8, st));
+    DSC_HIP(hipMemsetAsync(P.ysum, 0, (size_t)P.TP * 8, st));
+    k_targets<<<pb.T, 256, 0, st>>>(n, pb.T, pb.Y, pb.ldy, ldn, P.Yc, P.Yn, P.syy, P.ysum, P.bad);
+    check_launch("k_targets");
+    {
+        KTimer kt(ctx, st, "materialise");
+        for (size_t r = 0; r + 1 < sp.rung_start.size(); r++) {
+            const int c0 = sp.rung_start[r], c1 = sp.rung_start[r + 1];
+            if (c1 <= c0) continue;
+            dim3 g((unsigned)cdiv(n, 256), (unsigned)(c1 - c0));
+            k_mat_values<<<g, 256, 0, st>>>(n, ldn, c0, c1, pb.X, pb.ldx, pl.mat_op, pl.mat_a,
+                                            pl.mat_b, pl.mat_raw, P.Vf);
+            k_mat_stats<<<(unsigned)cdiv(c1 - c0, 4), 256, 0, st>>>(
+                n, ldn, c0, c1, pl.mat_a, pl.mat_b, P.Vf, P.Rf, P.Cf, P.mu, P.mur, P.valid);
+        }
+        check_launch("k_mat");
+    }
+    P.scores = ctx->buf<double>("scores", (size_t)P.Tl * N);
+    DSC_HIP(hipMemsetAsync(P.scores, 0xFF, (size_t)P.Tl * N * 8, st));
+    Ops ops{P.Vf, P.Rf, ldn};
     {
         KTimer kt(ctx, st, "screen_list");
-        k_score_list<<<(unsigned)cdiv((int64_t)items.size(), 4), 256, 0, st>>>(
-            d_items, (int64_t)items.size(), ops, P.valid, n, pb.T, prm.score_mode, P.Yc, P.syy, N,
-            P.scores, P.nscored);
+        k_score_list<<<(unsigned)cdiv(pl.n_items, 4), 256, 0, st>>>(
+            pl.items, pl.n_items, ops, P.valid, n, pb.T, prm.score_mode, P.Yc, P.syy, N, P.scores,
+            P.nscored);
         check_launch("k_score_list");
     }
-    if (!R) return;
-
-    // streamed binary candidates
+    const int R = sp.streamed;
+    if (!R || (!pl.dense_ops && !pl.list_ops)) return;
     P.Vs = ctx->buf<double>("Vs", (size_t)n * ldm);
     P.Rs = ctx->buf<double>("Rs", (size_t)n * ldm);
     P.Cs = ctx->buf<double>("Cs", (size_t)n * ldm);
@@ -947,98 +1194,37 @@ static void screen_problem(discover_ctx* ctx, const discover_problem& pb,
         k_transpose<<<g, b, 0, st>>>(n, Mc, ldn, ldm, P.Cf, P.Cs);
         check_launch("k_transpose");
     }
-    uint32_t bin = 0;
-    for (int o = OP_ADD; o <= OP_RDIV; o++)
-        if (sd.block[R][o] >= 0) bin |= 1u << (o - OP_ADD);
-    if (!bin) return;
-    const int32_t jc0 = sp.rung_start[R - 1], jc1 = sp.rung_start[R];
     const int pool = sd.pool[R];
-    const int32_t i_end = pool == R - 1 ? Mc : sp.rung_start[pool + 1];
-
     PairArgs a{};
-    a.n = n; a.ldm = ldm; a.ldn = ldn; a.Mc = Mc; a.jc_end = jc1; a.i_end = i_end;
+    a.n = n; a.ldm = ldm; a.ldn = ldn; a.Mc = Mc; a.jc_end = sp.rung_start[R];
+    a.i_end = pool == R - 1 ? Mc : sp.rung_start[pool + 1];
     a.Vs = P.Vs; a.Rs = P.Rs; a.Cs = P.Cs; a.Vf = P.Vf; a.Rf = P.Rf; a.Cf = P.Cf;
-    a.mu = P.mu; a.mur = P.mur; a.valid = P.valid; a.mat_raw = P.mat_raw;
+    a.mu = P.mu; a.mur = P.mur; a.valid = P.valid; a.mat_raw = pl.mat_raw;
     a.Yn = P.Yn; a.ysum = P.ysum; a.T = pb.T; a.mode = prm.score_mode; a.r = R;
     a.sd = sd; a.N = N; a.scores = P.scores; a.nscored = P.nscored;
     a.fix_cap = std::min<int64_t>(N, (int64_t)1 << 24);
     a.fix_ids = ctx->buf<int64_t>("fix_ids", a.fix_cap);
-    a.fix_cnt = ctx->buf<unsigned long long>("fix_cnt", 1);
-    DSC_HIP(hipMemsetAsync(a.fix_cnt, 0, 8, st));
-
-    // dense tiles: all pairs (no units) or the multiplicative class (units)
-    const bool units = sp.B > 0;
-    const uint32_t dense_ops = units ? (bin & 28u) : bin;
-    const uint32_t list_ops = units ? (bin & 3u) : 0u;
-    if (dense_ops) {
-        const int J = dense_J(P.TP);
-        std::vector<int2> tiles;
-        for (int32_t j = jc0; j < jc1; j += J) {
-            const int32_t ilim = std::min<int32_t>(i_end, std::min<int32_t>(j + J - 1, jc1 - 1));
-            for (int32_t i0 = 0; i0 < ilim; i0 += 64) tiles.push_back(make_int2(j, i0));
-        }
-        int2* d_t = ctx->buf<int2>("tiles", tiles.size());
-        upload(d_t, tiles, st);
-        a.tiles = d_t;
-        a.ilist = nullptr;
-        a.icount = nullptr;
-        a.n_tiles = (int64_t)tiles.size();
-        a.opmask = dense_ops;
-        const int cls = units ? 28 : 31;
+    a.fix_cnt = fix_cnt;
+    if (pl.dense_ops) {
+        a.tiles = pl.dtiles; a.ilist = nullptr; a.icount = nullptr;
+        a.n_tiles = pl.n_dtiles; a.opmask = pl.dense_ops;
         KTimer kt(ctx, st, "screen_pairs");
-        launch_pairs(cls, a, false, P.TP, st);
+        launch_pairs(pl.dense_cls, a, false, P.TP, st);
         check_launch("k_screen_pairs");
     }
-    if (list_ops) {
-        // same-unit partners below j (or inside the partner pool)
-        std::vector<int2> tiles;
-        std::vector<int32_t> il, ic;
-        std::map<std::string, std::vector<int32_t>> by_unit;
-        auto key = [&](int32_t c) {
-            return std::string((const char*)&sp.mat_unit[(size_t)c * Bq], sizeof(int32_t) * Bq);
-        };
-        if (pool != R - 1)
-            for (int32_t c = 0; c < i_end; c++) by_unit[key(c)].push_back(c);
-        for (int32_t c = 0; c < jc1; c++) {
-            if (c >= jc0) {
-                auto it = by_unit.find(key(c));
-                if (it != by_unit.end()) {
-                    const auto& v = it->second;
-                    for (size_t q = 0; q < v.size(); q += 64) {
-                        tiles.push_back(make_int2(c, (int)il.size()));
-                        const int cnt = (int)std::min<size_t>(64, v.size() - q);
-                        ic.push_back(cnt);
-                        il.insert(il.end(), v.begin() + q, v.begin() + q + cnt);
-                    }
-                }
-            }
-            if (pool == R - 1) by_unit[key(c)].push_back(c);
-        }
-        if (!tiles.empty()) {
-            int2* d_t = ctx->buf<int2>("ltiles", tiles.size());
-            int32_t* d_il = ctx->buf<int32_t>("ilist", il.size());
-            int32_t* d_ic = ctx->buf<int32_t>("icount", ic.size());
-            upload(d_t, tiles, st);
-            upload(d_il, il, st);
-            upload(d_ic, ic, st);
-            a.tiles = d_t;
-            a.ilist = d_il;
-            a.icount = d_ic;
-            a.n_tiles = (int64_t)tiles.size();
-            a.opmask = list_ops;
-            KTimer kt(ctx, st, "screen_pairs_list");
-            launch_pairs(3, a, true, P.TP, st);
-            check_launch("k_screen_pairs(list)");
-        }
+    if (pl.list_ops && pl.n_ltiles) {
+        a.tiles = pl.ltiles; a.ilist = pl.ilist; a.icount = pl.icount;
+        a.n_tiles = pl.n_ltiles; a.opmask = pl.list_ops;
+        KTimer kt(ctx, st, "screen_pairs_list");
+        launch_pairs(3, a, true, P.TP, st);
+        check_launch("k_screen_pairs(list)");
     }
-    // exact decision for the ill-conditioned ones (grid sized by the capacity,
-    // each wave exits when beyond the device-side count)
-    const unsigned long long nfix = download1(a.fix_cnt, st);
-    if (nfix > 0) {
-        const int64_t m = std::min<int64_t>((int64_t)nfix, a.fix_cap);
+    {
+        // exact decision for the ill-conditioned ones (persistent waves over
+        // the device-side count)
         KTimer kt(ctx, st, "screen_fixup");
-        k_fixup<DISCOVER_MAX_TARGETS><<<(unsigned)cdiv(m, 4), 256, 0, st>>>(
-            a.fix_ids, a.fix_cnt, a.fix_cap, sd, sp.streamed, P.raw2c, P.valid, ops, n, pb.T,
+        k_fixup<DISCOVER_MAX_TARGETS><<<1024, 256, 0, st>>>(
+            a.fix_ids, a.fix_cnt, a.fix_cap, sd, sp.streamed, pl.raw2c, P.valid, ops, n, pb.T,
             prm.score_mode, P.Yc, P.syy, N, P.scores, P.nscored);
         check_launch("k_fixup");
     }
@@ -1047,13 +1233,14 @@ static void screen_problem(discover_ctx* ctx, const discover_problem& pb,
 // Exact top-k of list t (pool, rescore, sort, duplicate groups).  The
 // pool holds every candidate whose score can reach the K-th largest
 // approximate score minus the error margin; it is rescored exactly and
-// scanned in (-score, ID) order.  If the scan leaves the region the pool
-// covers before k groups are final, K grows and the selection repeats.
+// grouped in (-score, ID) order.  If the pool does not reach below the
+// near-tie window of the k-th group, K grows and the selection repeats.
 static void select_list(discover_ctx* ctx, const discover_problem& pb,
                         const discover_screen_params& prm, Problem& P, int t, double margin,
                         int64_t* out_ids, double* out_sc, discover_screen_stats& stats,
                         hipStream_t st) {
-    const Space& sp = P.sp;
+    const Plan& pl = *P.plan;
+    const Space& sp = pl.sp;
     const int64_t N = sp.n_raw();
     const double* sc = P.scores + (int64_t)t * N;
     const int k = prm.k;
@@ -1062,68 +1249,78 @@ static void select_list(discover_ctx* ctx, const discover_problem& pb,
     uint32_t* sel = ctx->buf<uint32_t>("sel", 4);
     int64_t* stv = ctx->buf<int64_t>("selst", 2);
     unsigned long long* cnt = ctx->buf<unsigned long long>("poolcnt", 1);
-    int64_t* res = ctx->buf<int64_t>("groupres", 3);
+    int64_t* res = ctx->buf<int64_t>("groupres", 8);
     Ops ops{P.Vf, P.Rf, P.ldn};
-    const unsigned hb = (unsigned)std::min<int64_t>(1024, std::max<int64_t>(1, cdiv(N, 256 * 8)));
+    int64_t cap = 4 * K + 4096;
+    int64_t fcap = 64 * cap;
     for (;;) {
         {
             KTimer kt(ctx, st, "select");
             radix_select(sc, N, K, hist, sel, stv, st);
         }
-        int64_t cap = 4 * K + 65536;
-        int64_t P_n = 0;
-        int64_t* pool = nullptr;
-        for (;;) {
-            pool = ctx->buf<int64_t>("pool", cap);
-            DSC_HIP(hipMemsetAsync(cnt, 0, 8, st));
-            k_compact<<<hb, 256, 0, st>>>(sc, N, sel, stv, margin, cap, pool, cnt);
-            check_launch("k_compact");
-            P_n = (int64_t)download1(cnt, st);
-            if (P_n <= cap) break;
-            cap = P_n;
-        }
-        stats.pool_size += P_n;
-        double* ps = ctx->buf<double>("ps", P_n);
-        uint8_t* pex = ctx->buf<uint8_t>("pex", P_n);
-        int32_t* order = ctx->buf<int32_t>("order", P_n);
-        int32_t* lo = ctx->buf<int32_t>("wlo", P_n);
-        int32_t* wc = ctx->buf<int32_t>("wcnt", P_n);
-        int64_t* off = ctx->buf<int64_t>("woff", P_n + 1);
-        if (P_n > 0) {
+        int64_t* pool = ctx->buf<int64_t>("pool", cap);
+        double* ps = ctx->buf<double>("ps", cap);
+        uint8_t* pex = ctx->buf<uint8_t>("pex", cap);
+        int32_t* order = ctx->buf<int32_t>("order", cap);
+        int32_t* lo = ctx->buf<int32_t>("wlo", cap);
+        int32_t* wc = ctx->buf<int32_t>("wcnt", cap);
+        int64_t* off = ctx->buf<int64_t>("woff", cap + 1);
+        uint8_t* flag = ctx->buf<uint8_t>("dupflag", fcap);
+        int32_t* parent = ctx->buf<int32_t>("gparent", cap + 1);
+        int32_t* blk = ctx->buf<int32_t>("gblk", cap + 1);
+        unsigned long long* repid = ctx->buf<unsigned long long>("grepid", cap + 1);
+        int32_t* reppos = ctx->buf<int32_t>("greppos", cap + 1);
+        int32_t* headpos = ctx->buf<int32_t>("gheadpos", (size_t)k + 1);
+        DSC_HIP(hipMemsetAsync(cnt, 0, 8, st));
+        const unsigned hb = (unsigned)std::min<int64_t>(1024, std::max<int64_t>(1, cdiv(N, 256 * 8)));
+        k_compact<<<hb, 256, 0, st>>>(sc, N, sel, stv, margin, cap, pool, cnt);
+        check_launch("k_compact");
+        {
             KTimer kt(ctx, st, "rescore");
-            k_rescore<DISCOVER_MAX_TARGETS><<<(unsigned)cdiv(P_n, 4), 256, 0, st>>>(
-                pool, P_n, sp.d, sp.streamed, P.raw2c, P.valid, ops, P.n, P.T, prm.score_mode, t,
+            k_rescore<DISCOVER_MAX_TARGETS><<<(unsigned)std::min<int64_t>(2048, cdiv(cap, 4)), 256, 0, st>>>(
+                pool, cnt, cap, sp.d, sp.streamed, pl.raw2c, P.valid, ops, P.n, P.T, prm.score_mode, t,
                 P.Yc, P.syy, pb.exclude, pb.exclude ? pb.n_exclude : 0, ps, pex);
             check_launch("k_rescore");
         }
-        int64_t npairs = 0;
         {
             KTimer kt(ctx, st, "sort_dedup");
-            if (P_n > 0) {
-                k_rank<<<(unsigned)cdiv(P_n, 256), 256, 0, st>>>(ps, pool, P_n, order);
-                k_window<<<(unsigned)cdiv(P_n, 256), 256, 0, st>>>(ps, order, P_n, lo, wc);
-                k_scan_offsets<<<1, 1024, 0, st>>>(wc, P_n, off);
-                check_launch("k_rank");
-                npairs = download1(off + P_n, st);
-            }
+            k_bitonic<<<1, 1024, 0, st>>>(ps, pool, cnt, cap, order);
+            k_rank<<<(unsigned)cdiv(cap, 256), 256, 0, st>>>(ps, pool, cnt, cap, order);
+            k_window<<<(unsigned)std::min<int64_t>(1024, cdiv(cap, 256)), 256, 0, st>>>(ps, order, cnt, cap, lo, wc);
+            k_scan_offsets<<<1, 1024, 0, st>>>(wc, cnt, cap, off);
+            check_launch("k_sort");
         }
-        uint8_t* flag = ctx->buf<uint8_t>("dupflag", npairs);
-        if (npairs > 0 && prm.dedup) {
+        if (prm.dedup) {
             KTimer kt(ctx, st, "dedup_pairs");
-            k_pairs<<<(unsigned)cdiv(npairs, 4), 256, 0, st>>>(pool, order, lo, off, P_n, sp.d,
-                                                               sp.streamed, P.raw2c, ops, P.n, flag);
+            k_pairs<<<2048, 256, 0, st>>>(pool, order, lo, off, cnt, cap, sp.d, sp.streamed, pl.raw2c,
+                                          ops, P.n, flag, fcap);
             check_launch("k_pairs");
         }
-        int32_t* hpos = ctx->buf<int32_t>("hpos", P_n + 1);
-        uint8_t* hblk = ctx->buf<uint8_t>("hblk", P_n + 1);
-        int64_t* hmin = ctx->buf<int64_t>("hmin", P_n + 1);
-        double* hsc = ctx->buf<double>("hsc", P_n + 1);
-        k_groups<<<1, 64, 0, st>>>(pool, ps, pex, order, lo, off, flag, P_n, k, prm.dedup, sel,
-                                   stv, margin, hpos, hblk, hmin, hsc, out_ids, out_sc, res);
-        check_launch("k_groups");
-        int64_t h_res[3];
+        {
+            KTimer kt(ctx, st, "groups");
+            k_groups<<<1, GRP_THREADS, 0, st>>>(pool, ps, pex, order, lo, off, flag, cnt, cap, fcap, k,
+                                                prm.dedup, sel, stv, margin, parent, blk, repid,
+                                                reppos, headpos, out_ids, out_sc, res);
+            check_launch("k_groups");
+        }
+        int64_t h_res[8];
+        int h_bad = 0;
         DSC_HIP(hipMemcpyAsync(h_res, res, sizeof h_res, hipMemcpyDeviceToHost, st));
+        DSC_HIP(hipMemcpyAsync(&h_bad, P.bad, sizeof h_bad, hipMemcpyDeviceToHost, st));
         DSC_HIP(hipStreamSynchronize(st));
+        if (h_bad) DSC_FAIL(DISCOVER_E_NUMERIC, "a target column is constant or not finite");
+        if (h_res[4] > cap) {                       // pool overflow: enlarge and redo
+            cap = h_res[4] + 1024;
+            fcap = std::max(fcap, 64 * cap);
+            stats.pool_rounds += 1;
+            continue;
+        }
+        if (prm.dedup && h_res[3] > fcap) {         // pair-flag overflow
+            fcap = h_res[3] + 1024;
+            stats.pool_rounds += 1;
+            continue;
+        }
+        stats.pool_size += h_res[4];
         if (h_res[1] || K >= N) {
             stats.n_selected += h_res[0];
             stats.n_merged += h_res[2];
@@ -1131,6 +1328,8 @@ static void select_list(discover_ctx* ctx, const discover_problem& pb,
         }
         stats.pool_rounds += 1;
         K = std::min<int64_t>(N, K * 4);
+        cap = 4 * K + 4096;
+        fcap = std::max(fcap, 64 * cap);
     }
 }
 
@@ -1186,8 +1385,8 @@ extern "C" discover_status discover_generate_screen(discover_ctx* ctx, const dis
             Problem P{};
             discover_screen_stats stats{};
             screen_problem(ctx, pb, *prm, P, st);
-            stats.n_raw = P.sp.n_raw();
-            stats.n_unit_valid = P.sp.n_unit_valid;
+            stats.n_raw = P.plan->sp.n_raw();
+            stats.n_unit_valid = P.plan->sp.n_unit_valid;
             const double margin = 4.0 * P.n * EPS64 * KAPPA_MAX;
             const int Tl = P.Tl;
             for (int t = 0; t < Tl; t++) {
@@ -1198,8 +1397,8 @@ extern "C" discover_status discover_generate_screen(discover_ctx* ctx, const dis
                 KTimer kt(ctx, st, "values");
                 Ops ops{P.Vf, P.Rf, P.ldn};
                 const int64_t m = (int64_t)Tl * prm->k;
-                k_values<<<(unsigned)cdiv(m, 4), 256, 0, st>>>(out_ids + row * prm->k, m, P.sp.d,
-                                                               P.sp.streamed, P.raw2c, ops, P.n,
+                k_values<<<(unsigned)cdiv(m, 4), 256, 0, st>>>(out_ids + row * prm->k, m, P.plan->sp.d,
+                                                               P.plan->sp.streamed, P.plan->raw2c, ops, P.n,
                                                                out_values + row * prm->k * ldv, ldv);
                 check_launch("k_values");
             }
