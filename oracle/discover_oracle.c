@@ -53,6 +53,10 @@ enum { ST_VALID = 0, ST_UNIT = 1, ST_CHILD = 2, ST_NONFINITE = 3,
 /* A feature is numerically constant when its population standard deviation
  * is at most this fraction of its root-mean-square value. */
 static const double OR_CONST_TOL = 1e-8;
+/* A sum or difference whose root-mean-square value is at most this fraction
+ * of its operands' combined root-mean-square value is cancellation noise
+ * (e.g. x - exp(log(x))) and counts as constant. */
+static const double OR_CANCEL_TOL = 1e-10;
 
 /* ------------------------------------------------------------------------ */
 /* Search-space description                                                  */
@@ -282,6 +286,16 @@ static int feature_checks(int n, const double* f, double* tmp, double* mean, dou
     return ST_VALID;
 }
 
+/* Cancellation rule for add/sub: sum f^2 <= tol^2 (sum a^2 + sum b^2). */
+static int cancelled(int o, int n, const double* f, const double* a, const double* b, double* tmp) {
+    if (o != OP_ADD && o != OP_SUB) return 0;
+    for (int s = 0; s < n; s++) tmp[s] = f[s] * f[s];
+    const double ff = nsum(tmp, n);
+    for (int s = 0; s < n; s++) tmp[s] = a[s] * a[s] + b[s] * b[s];
+    const double ab = nsum(tmp, n);
+    return ff <= OR_CANCEL_TOL * OR_CANCEL_TOL * ab;
+}
+
 /* Pearson r of f against a centered target yc (sum of squares syy):
  * two-pass, compensated, r = sum (f-m)(yc) / sqrt(sxx * syy). */
 static double pearson(int n, const double* f, double m, double sxx,
@@ -344,6 +358,9 @@ int64_t or_screen(int n, int p, const double* X, int T, const double* Y,
         else {
             double m, sxx;
             status[t] = (uint8_t)feature_checks(n, V + t * n, tmp0, &m, &sxx);
+            if (status[t] == ST_VALID && ib[t] >= 0 &&
+                cancelled(op[t], n, V + t * n, V + ia[t] * n, V + ib[t] * n, tmp0))
+                status[t] = ST_CONST;
         }
     }
     #pragma omp parallel
@@ -361,6 +378,9 @@ int64_t or_screen(int n, int p, const double* X, int T, const double* Y,
                 apply_op(op[t], n, V + ia[t] * n, ib[t] >= 0 ? V + ib[t] * n : NULL, f);
                 double m, sxx;
                 status[t] = (uint8_t)feature_checks(n, f, tmp, &m, &sxx);
+                if (status[t] == ST_VALID && ib[t] >= 0 &&
+                    cancelled(op[t], n, f, V + ia[t] * n, V + ib[t] * n, tmp))
+                    status[t] = ST_CONST;
                 if (status[t] != ST_VALID) goto fill;
                 fv = f;
                 for (int q = 0; q < T; q++)
@@ -406,9 +426,16 @@ static int eval_rec(const space_t* s, int n, const double* X, int B,
         int sb = b >= 0 ? eval_rec(s, n, X, B, units, b, fb, ub, tmp) : ST_VALID;
         int leg = (sa != ST_UNIT) && (sb != ST_UNIT) && unit_rule(o, B, ua, ub, u);
         apply_op(o, n, fa, fb, f);         /* values are returned in every case */
+        int st = ST_VALID;
+        if (!leg) { for (int k = 0; k < B; k++) u[k] = 0; st = ST_UNIT; }
+        else if (sa != ST_VALID || sb != ST_VALID) st = ST_CHILD;
+        else {
+            double m, sxx;
+            st = feature_checks(n, f, tmp, &m, &sxx);
+            if (st == ST_VALID && fb && cancelled(o, n, f, fa, fb, tmp)) st = ST_CONST;
+        }
         free(fa); free(fb);
-        if (!leg) { for (int k = 0; k < B; k++) u[k] = 0; return ST_UNIT; }
-        if (sa != ST_VALID || sb != ST_VALID) return ST_CHILD;
+        return st;
     }
     double m, sxx;
     return feature_checks(n, f, tmp, &m, &sxx);

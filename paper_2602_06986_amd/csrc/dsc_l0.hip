@@ -48,11 +48,13 @@ __global__ __launch_bounds__(256) void k_l0_prep(int n, int S, const double* __r
     if (row == S && lane == 0) *yy = q;
 }
 
-// G = Z Z^T for (S+1) rows, 64x64 tiles, 4x4 outputs per thread, samples
-// staged through LDS in chunks of 16.
+// G = Z Z^T for (S+1) rows: 64x64 tiles (upper triangle only, mirrored),
+// 4x4 outputs per thread, samples staged through LDS in chunks of 16 and
+// read back as double2 pairs.
 __global__ __launch_bounds__(256) void k_gram(int M, int ldz, int nk, const double* __restrict__ Z,
                                               double* __restrict__ G, int ldg) {
-    __shared__ double As[16][65], Bs[16][65];
+    __shared__ __align__(16) double As[16][64];
+    __shared__ __align__(16) double Bs[16][64];
     const int bi = blockIdx.y * 64, bj = blockIdx.x * 64;
     if (bj + 63 < bi) return;                 // lower triangle mirrored below
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
@@ -67,12 +69,12 @@ __global__ __launch_bounds__(256) void k_gram(int M, int ldz, int nk, const doub
         __syncthreads();
 #pragma unroll
         for (int kk = 0; kk < 16; kk++) {
-            double a[4], b[4];
-#pragma unroll
-            for (int u = 0; u < 4; u++) {
-                a[u] = As[kk][ty * 4 + u];
-                b[u] = Bs[kk][tx * 4 + u];
-            }
+            const double2 a01 = *(const double2*)&As[kk][ty * 4];
+            const double2 a23 = *(const double2*)&As[kk][ty * 4 + 2];
+            const double2 b01 = *(const double2*)&Bs[kk][tx * 4];
+            const double2 b23 = *(const double2*)&Bs[kk][tx * 4 + 2];
+            const double a[4] = {a01.x, a01.y, a23.x, a23.y};
+            const double b[4] = {b01.x, b01.y, b23.x, b23.y};
 #pragma unroll
             for (int u = 0; u < 4; u++)
 #pragma unroll
@@ -152,15 +154,17 @@ __global__ __launch_bounds__(256) void k_sweep2(SweepArgs g) {
     g.lane_q[it * 64 + lane] = (b < g.S && b > a) ? q2(g.G, g.ldg, g.S, a, b) : -1.0;
 }
 
-// D = 3: one block = fixed a and 256 consecutive c (4 waves, lane c), loop
-// over a < b < c.  Per b (uniform, staged in LDS): u_b = G[a][b],
+// D = 3.  One block = 16 consecutive a (4 per wave) x 64 consecutive c (one
+// per lane), looping over b.  Each G[b][c] load serves the wave's 4 values
+// of a.  Per (a, b) (uniform, staged in LDS): u_b = G[a][b],
 // g_b = z'_b / d_b, h_b = 1 / d_b, Q_ab = c_a^2 / G_aa + z'_b^2 / d_b with
 // d_b = G_bb - u_b^2 / G_aa and z'_b = c_b - u_b c_a / G_aa.  Per subset:
 //   C'  = G[b][c] - u_b u_c / G_aa
 //   den = d_c - C'^2 / d_b            (third Cholesky pivot)
 //   e   = z'_c - C' g_b
 //   q   = Q_ab + e^2 / den.
-constexpr int SW3_CHUNK = 1024;       // b entries staged in LDS at a time (32 KB)
+constexpr int SW3_A = 4;              // values of a per wave
+constexpr int SW3_CHUNK = 64;         // b entries staged per a and chunk (16 x 64 x 32 B = 32 KB)
 
 struct Sw3Lane {
     double upc, dc, zc;
@@ -188,51 +192,78 @@ __device__ __forceinline__ double sw3_q(const double4& e, const Sw3Lane& L, doub
 }
 
 __global__ __launch_bounds__(256) void k_sweep3(SweepArgs g) {
-    __shared__ double4 tab[SW3_CHUNK];
+    __shared__ double4 tab[4 * SW3_A][SW3_CHUNK];
     const int2 item = g.items[blockIdx.x];
-    const int a = item.x;
-    double* out = g.lane_q + (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (a < 0) {                                         // padding block (uniform)
-        *out = -1.0;
+    const int a0 = item.x, c0 = item.y;                  // block: a0..a0+15, c0..c0+63
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int c = c0 + lane;
+    double* out = g.lane_q + ((int64_t)blockIdx.x * 4 + wv) * (SW3_A * 64);
+    if (a0 < 0) {                                        // padding block (uniform)
+        for (int k = 0; k < SW3_A; k++) out[k * 64 + lane] = -1.0;
         return;
     }
-    const double* Ga = g.G + (int64_t)a * g.ldg;
-    const double caa = Ga[a], ca = Ga[g.S];
-    const int c = item.y + threadIdx.x;
-    if (!(caa > PIV_TOL)) {                              // uniform
-        *out = -1.0;
-        return;
-    }
-    const double ica = 1.0 / caa;
     const bool cok = c < g.S;
-    const int cc = cok ? c : a;
-    Sw3Lane L;
-    const double uc = Ga[cc];
-    L.upc = uc * ica;
-    L.dc = g.G[(int64_t)cc * g.ldg + cc] - uc * L.upc;
-    L.zc = g.G[(int64_t)cc * g.ldg + g.S] - ca * L.upc;
-    const int wave_c0 = item.y + (threadIdx.x & ~63);
-    const int bend = min(g.S, wave_c0 + 64) - 1;         // b < the wave's largest c
-    const int bend_blk = min(g.S, item.y + 256) - 1;
+    const int cc = cok ? c : g.S - 1;
+    const double Gcc = g.G[(int64_t)cc * g.ldg + cc], cyc = g.G[(int64_t)cc * g.ldg + g.S];
+    Sw3Lane L[SW3_A];
+    double best[SW3_A];
+    int av[SW3_A];
+    bool aok[SW3_A];
+#pragma unroll
+    for (int k = 0; k < SW3_A; k++) {
+        const int a = a0 + wv * SW3_A + k;
+        av[k] = a;
+        const int ac = a < g.S ? a : g.S - 1;
+        const double* Ga = g.G + (int64_t)ac * g.ldg;
+        const double caa = Ga[ac], ca = Ga[g.S];
+        aok[k] = a < g.S - 2 && caa > PIV_TOL;
+        const double ica = 1.0 / caa;
+        const double uc = Ga[cc];
+        L[k].upc = uc * ica;
+        L[k].dc = Gcc - uc * L[k].upc;
+        L[k].zc = cyc - ca * L[k].upc;
+        best[k] = -1.0;
+    }
     const double* colc = g.G + cc;
-    double best = -1.0;
-    for (int b0 = a + 1; b0 < bend_blk; b0 += SW3_CHUNK) {
-        const int nb = min(SW3_CHUNK, bend_blk - b0);
+    const int bend = min(g.S - 1, c0 + 63);              // b < largest c of the block
+    for (int b0 = a0 + 1; b0 < bend; b0 += SW3_CHUNK) {
+        const int nb = min(SW3_CHUNK, bend - b0);
         __syncthreads();
-        for (int t = threadIdx.x; t < nb; t += 256)
-            tab[t] = sw3_b_entry(g.G, g.ldg, g.S, Ga, ica, ca, b0 + t);
+        // stage (a, b) factors for the block's 16 values of a
+        for (int t = threadIdx.x; t < 4 * SW3_A * nb; t += 256) {
+            const int ka = t / nb, bb = b0 + t % nb;
+            const int a = a0 + ka;
+            double4 e = make_double4(0.0, 0.0, 0.0, -INFINITY);   // b <= a or singular: q = -inf
+            if (a < g.S - 2 && bb > a) {
+                const double* Ga = g.G + (int64_t)a * g.ldg;
+                const double caa = Ga[a];
+                if (caa > PIV_TOL) {
+                    e = sw3_b_entry(g.G, g.ldg, g.S, Ga, 1.0 / caa, Ga[g.S], bb);
+                    if (e.w < 0.0) e.w = -INFINITY;
+                }
+            }
+            tab[ka][t % nb] = e;
+        }
         __syncthreads();
-        const int bl = min(b0 + nb, bend);
-        for (int b = b0; b < bl; b++) {
-            const double4 e = tab[b - b0];
-            if (e.w < 0.0) continue;                      // uniform: singular (a, b)
-            double den;
-            const double q = sw3_q(e, L, colc[(int64_t)b * g.ldg], den);
-            const bool ok = cok && (b < c) && (den > PIV_TOL);
-            best = fmax(best, ok ? pack_q(q, b) : -1.0);
+        // branch-free inner loop; G[b][c] of the next b is loaded ahead
+        double Cnext = colc[(int64_t)b0 * g.ldg];
+        for (int b = b0; b < b0 + nb; b++) {
+            const double Cbc = Cnext;
+            Cnext = colc[(int64_t)min(b + 1, g.S - 1) * g.ldg];
+            const bool bc = cok && b < c;
+#pragma unroll
+            for (int k = 0; k < SW3_A; k++) {
+                const double4 e = tab[wv * SW3_A + k][b - b0];
+                double den;
+                const double q = sw3_q(e, L[k], Cbc, den);
+                const double v = (bc && den > PIV_TOL) ? q : -INFINITY;
+                best[k] = v > best[k] ? v : best[k];
+            }
         }
     }
-    *out = best;
+#pragma unroll
+    for (int k = 0; k < SW3_A; k++) out[k * 64 + lane] = best[k];
+    (void)av;
 }
 
 // Band expansion.  thr = (m-th best lane value) * (1 - 1e-12) - GRAM_DELTA.
@@ -264,7 +295,7 @@ __device__ __forceinline__ void band_push(const BandArgs& g, int a, int b, int c
 
 __global__ __launch_bounds__(256) void k_band_lanes(BandArgs g) {
     const double thr = band_thr(g);
-    const int per = g.D == 3 ? 256 : 64;
+    const int per = g.D == 3 ? 4 * SW3_A * 64 : 64;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < g.n_lanes;
          i += (int64_t)gridDim.x * 256) {
         const double q = g.lane_q[i];
@@ -274,18 +305,20 @@ __global__ __launch_bounds__(256) void k_band_lanes(BandArgs g) {
         if (g.D == 1) band_push(g, it.y + lane, -1, -1);
         else if (g.D == 2) band_push(g, it.x, it.y + lane, -1);
         else {
+            // lane index within a D = 3 block: ((wave * SW3_A) + k) * 64 + c lane
+            const int wk = lane / 64, cl = lane % 64;
             const unsigned long long slot = atomicAdd(g.pcnt, 1ull);
-            if ((int64_t)slot < g.pcap) g.pairs[slot] = make_int2(it.x, it.y + lane);
+            if ((int64_t)slot < g.pcap) g.pairs[slot] = make_int2(it.x + wk, it.y + cl);
         }
     }
 }
 
-// D = 3: one thread per listed (a, c) lane, every b with q >= thr.
+// D = 3: one wave per listed (a, c) lane; its lanes split the b range.
 __global__ __launch_bounds__(256) void k_band_expand3(BandArgs g) {
     const double thr = band_thr(g);
     const int64_t np = min((int64_t)*g.pcnt, g.pcap);
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < np;
-         i += (int64_t)gridDim.x * 256) {
+    const int lane = threadIdx.x & 63;
+    for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < np; i += (int64_t)gridDim.x * 4) {
         const int a = g.pairs[i].x, c = g.pairs[i].y;
         const double* Ga = g.G + (int64_t)a * g.ldg;
         const double caa = Ga[a], ca = Ga[g.S];
@@ -295,7 +328,7 @@ __global__ __launch_bounds__(256) void k_band_expand3(BandArgs g) {
         L.upc = uc * ica;
         L.dc = g.G[(int64_t)c * g.ldg + c] - uc * L.upc;
         L.zc = g.G[(int64_t)c * g.ldg + g.S] - ca * L.upc;
-        for (int b = a + 1; b < c; b++) {
+        for (int b = a + 1 + lane; b < c; b += 64) {
             const double4 e = sw3_b_entry(g.G, g.ldg, g.S, Ga, ica, ca, b);
             if (e.w < 0.0) continue;
             double den;
@@ -559,13 +592,15 @@ __global__ __launch_bounds__(256) void k_omp_fit(int n, const double* __restrict
     }
 }
 
-__global__ void k_row_norm(int S, int ldz, const double* __restrict__ Z, int n,
-                           double* __restrict__ nrm) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_row_norm(int S, int ldz, const double* __restrict__ Z, int n,
+                                                  double* __restrict__ nrm) {
+    const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (j >= S) return;
     double s = 0.0;
-    for (int i = 0; i < n; i++) s += Z[(int64_t)j * ldz + i] * Z[(int64_t)j * ldz + i];
-    nrm[j] = s;
+    for (int i = lane; i < n; i += 64) s += Z[(int64_t)j * ldz + i] * Z[(int64_t)j * ldz + i];
+    s = wave_sum(s);
+    if (lane == 0) nrm[j] = s;
 }
 
 // ================================================================== host
@@ -591,19 +626,32 @@ static void prep_gram(discover_ctx* ctx, const discover_l0_problem& pb, L0Plan& 
     check_launch("k_gram");
 }
 
-// D = 3 blocks (a, 256 consecutive c), ordered so that block p runs on XCD
-// p mod 8 and every XCD sees only the c-groups g with g mod 8 == its index:
-// each XCD's L2 then holds 1/8 of the Gram columns.  Within an XCD queue the
-// heaviest blocks (most b iterations) go first.
+// D = 3 blocks (16 consecutive a, 64 consecutive c).  Column groups of 64
+// are dealt to the 8 XCDs by longest-processing-time on their total work,
+// and block p of the grid runs on XCD p mod 8, so each XCD's L2 holds only
+// its own columns of G; within an XCD the heaviest blocks go first.
 static std::vector<int2> sweep3_blocks(int S) {
-    std::vector<std::vector<std::pair<int64_t, int2>>> q(8);
-    for (int a = 0; a < S - 2; a++)
-        for (int c0 = ((a + 2) / 256) * 256; c0 < S; c0 += 256) {
-            const int cl = std::max(c0, a + 2), ch = std::min(S, c0 + 256);
-            if (cl >= ch) continue;
-            const int64_t work = (int64_t)(ch - 1 - a);
-            q[(c0 / 256) % 8].push_back({work, make_int2(a, c0)});
+    const int ngrp = (S + 63) / 64;
+    std::vector<std::vector<std::pair<int64_t, int2>>> per_grp(ngrp);
+    std::vector<int64_t> gwork(ngrp, 0);
+    for (int g = 0; g < ngrp; g++) {
+        const int c0 = 64 * g, ch = std::min(S, c0 + 64);
+        for (int a0 = 0; a0 < S - 2 && a0 + 2 < ch; a0 += 16) {
+            const int64_t work = (int64_t)(ch - 1 - a0) * 16;
+            per_grp[g].push_back({work, make_int2(a0, c0)});
+            gwork[g] += work;
         }
+    }
+    std::vector<int> order(ngrp);
+    for (int g = 0; g < ngrp; g++) order[g] = g;
+    std::sort(order.begin(), order.end(), [&](int x, int y) { return gwork[x] > gwork[y]; });
+    std::vector<std::vector<std::pair<int64_t, int2>>> q(8);
+    std::vector<int64_t> xwork(8, 0);
+    for (int g : order) {
+        const int x = (int)(std::min_element(xwork.begin(), xwork.end()) - xwork.begin());
+        xwork[x] += gwork[g];
+        q[x].insert(q[x].end(), per_grp[g].begin(), per_grp[g].end());
+    }
     size_t mx = 0;
     for (auto& v : q) {
         std::stable_sort(v.begin(), v.end(), [](const std::pair<int64_t, int2>& x,
@@ -634,7 +682,7 @@ static void l0_problem(discover_ctx* ctx, const discover_l0_problem& pb, int D, 
             for (int b0 = a + 1; b0 < S; b0 += 64) items.push_back(make_int2(a, b0));
     } else {
         items = sweep3_blocks(S);
-        per = 256;
+        per = 4 * SW3_A * 64;
     }
     const int64_t ni = (int64_t)items.size();
     const int64_t nl = ni * per;
@@ -669,7 +717,7 @@ static void l0_problem(discover_ctx* ctx, const discover_l0_problem& pb, int D, 
             KTimer kt(ctx, st, "l0_band");
             radix_select(g.lane_q, nl, m, hist, sel, sst, st);
             k_band_lanes<<<(unsigned)std::min<int64_t>(1024, cdiv(nl, 256)), 256, 0, st>>>(bg);
-            if (D == 3) k_band_expand3<<<256, 256, 0, st>>>(bg);
+            if (D == 3) k_band_expand3<<<1024, 256, 0, st>>>(bg);
             check_launch("k_band");
         }
         // refit every band subset by QR (persistent blocks over the device count)
@@ -786,7 +834,7 @@ extern "C" discover_status discover_omp(discover_ctx* ctx, const discover_l0_pro
             KTimer kt(ctx, st, "omp");
             k_l0_prep<<<(unsigned)cdiv(pb.S + 1, 4), 256, 0, st>>>(pb.n, pb.S, pb.F, pb.ldf, pb.y,
                                                                    L.ldz, L.Z, L.yy);
-            k_row_norm<<<(unsigned)cdiv(pb.S, 256), 256, 0, st>>>(pb.S, L.ldz, L.Z, pb.n, nrm);
+            k_row_norm<<<(unsigned)cdiv(pb.S, 4), 256, 0, st>>>(pb.S, L.ldz, L.Z, pb.n, nrm);
             DSC_HIP(hipMemsetAsync(active, 0xFF, (size_t)D_max * 4, st));
             if (n_init)
                 DSC_HIP(hipMemcpyAsync(active, init_active + (int64_t)b * n_init, (size_t)n_init * 4,

@@ -23,6 +23,7 @@
 #include "dsc_space.h"
 
 #include <memory>
+#include <type_traits>
 
 namespace dsc {
 
@@ -30,6 +31,7 @@ constexpr double TAU_CONST = 1e-8;   // std <= TAU_CONST * rms  => constant
 constexpr double TAU_NEAR = 1e-9;    // relative score window of a duplicate pair
 constexpr double TAU_DUP = 1e-9;     // 1 - |corr| at or below which two features are duplicates
 constexpr double KAPPA_MAX = 64.0;   // shifted-moment conditioning accepted without inflation
+constexpr double TAU_CANCEL = 1e-10; // add/sub with rms <= TAU_CANCEL * operand rms => constant
 constexpr double EPS64 = 1.1102230246251565e-16;
 
 // ------------------------------------------------------------------ targets
@@ -114,11 +116,12 @@ __global__ void k_mat_values(int n, int ldn, int c0, int c1, const double* __res
 // One wave per operand feature of one rung: validity, mean, reciprocals,
 // centered values.
 __global__ __launch_bounds__(256) void k_mat_stats(int n, int ldn, int c0, int c1,
+                                                   const int8_t* __restrict__ mop,
                                                    const int32_t* __restrict__ ca,
                                                    const int32_t* __restrict__ cb,
                                                    double* __restrict__ Vf, double* __restrict__ Rf,
                                                    double* __restrict__ Cf, double* __restrict__ mu,
-                                                   double* __restrict__ mur,
+                                                   double* __restrict__ mur, double* __restrict__ msq,
                                                    uint8_t* __restrict__ valid) {
     const int c = c0 + blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -145,15 +148,30 @@ __global__ __launch_bounds__(256) void k_mat_stats(int n, int ldn, int c0, int c
         q += d * d;
     }
     q = wave_sum(q);
+    // cancellation rule for sums and differences
+    const int o = mop[c];
+    double ff = 0.0, ab = 0.0;
+    if ((o == OP_ADD || o == OP_SUB) && cb[c] >= 0) {
+        const double* va = Vf + (int64_t)ca[c] * ldn;
+        const double* vb = Vf + (int64_t)cb[c] * ldn;
+        for (int i = lane; i < n; i += 64) {
+            ff += v[i] * v[i];
+            ab += va[i] * va[i] + vb[i] * vb[i];
+        }
+        ff = wave_sum(ff);
+        ab = wave_sum(ab);
+    }
     if (lane == 0) {
         bool ok = !anybad && isfinite(q);
         const double sd = sqrt(q / n), rms = sqrt(q / n + m * m);
         ok = ok && (sd > TAU_CONST * rms);
+        if ((o == OP_ADD || o == OP_SUB) && cb[c] >= 0) ok = ok && !(ff <= TAU_CANCEL * TAU_CANCEL * ab);
         if (ca[c] >= 0) ok = ok && valid[ca[c]];
         if (cb[c] >= 0) ok = ok && valid[cb[c]];
         valid[c] = ok;
         mu[c] = m;
         mur[c] = sr / n;
+        msq[c] = q / n + m * m;
     }
 }
 
@@ -181,40 +199,66 @@ struct Ops {           // operand arrays of one problem
 };
 
 struct Cand {
-    int kind;          // 0 operand feature, 1 unary, 2 binary
+    int kind;          // 0 operand feature, 1 unary, 2 binary, 3 binary over a rung-2 operand
     int op;
-    int ca, cb;        // compact operand indices
+    int ca, cb;        // compact operand indices (kind 3: ca = first operand)
+    int op2, cc, cd;   // kind 3: rung-2 operand = op2(cc, cd) (cd = -1 for unary op2)
 };
 
-__device__ __forceinline__ double cand_value(const Cand& c, const Ops& o, int s) {
-    const double a = o.Vf[(int64_t)c.ca * o.ldn + s];
-    if (c.kind == 0) return a;
-    if (c.kind == 1) {
-        if (c.op == OP_INV) return o.Rf[(int64_t)c.ca * o.ldn + s];   // = 1.0 / a
-        return apply_op(c.op, a, 0.0);
-    }
-    const double b = o.Vf[(int64_t)c.cb * o.ldn + s];
-    return apply_op(c.op, a, b);
+// Everything needed to rebuild a candidate from its ID on the device.
+struct EvalCtx {
+    SpaceDev sd;
+    int streamed;                 // rung streamed by the pair kernels (operands below it in HBM)
+    int stream3;                  // operator-limited rung 3 streamed on top of rung 2
+    const int32_t* raw2c;         // raw -> compact operand index
+    const uint8_t* valid;         // operand validity
+    const uint8_t* r2_valid;      // stream3: validity of rung-2 features, by id - off[2]
+};
+
+__device__ __forceinline__ double unary_value(int op, const Ops& o, int c, int s) {
+    if (op == OP_INV) return o.Rf[(int64_t)c * o.ldn + s];         // = 1.0 / a
+    return apply_op(op, o.Vf[(int64_t)c * o.ldn + s], 0.0);
 }
 
-__device__ __forceinline__ bool cand_of_id(const SpaceDev& sd, int streamed,
-                                           const int32_t* __restrict__ raw2c, int64_t id, Cand& c) {
+__device__ __forceinline__ double cand_value(const Cand& c, const Ops& o, int s) {
+    if (c.kind == 1) return unary_value(c.op, o, c.ca, s);
+    const double a = o.Vf[(int64_t)c.ca * o.ldn + s];
+    if (c.kind == 0) return a;
+    if (c.kind == 2) return apply_op(c.op, a, o.Vf[(int64_t)c.cb * o.ldn + s]);
+    const double f2 = c.cd < 0 ? unary_value(c.op2, o, c.cc, s)
+                               : apply_op(c.op2, o.Vf[(int64_t)c.cc * o.ldn + s],
+                                          o.Vf[(int64_t)c.cd * o.ldn + s]);
+    return apply_op(c.op, a, f2);
+}
+
+// Decode an ID into an evaluable candidate; false when an operand is not an
+// operand feature (unit-illegal) or is invalid.
+__device__ __forceinline__ bool cand_of_id(const EvalCtx& e, int64_t id, Cand& c) {
     int rung, op;
     int64_t a, b;
-    decode_id(sd, id, rung, op, a, b);
-    if (streamed == 0 || rung < streamed) {
-        c.kind = 0; c.op = OP_NONE; c.ca = raw2c[id]; c.cb = -1;
-        return c.ca >= 0;
+    decode_id(e.sd, id, rung, op, a, b);
+    c.op2 = OP_NONE; c.cc = -1; c.cd = -1;
+    if (e.streamed == 0 || rung < e.streamed) {
+        c.kind = 0; c.op = OP_NONE; c.ca = e.raw2c[id]; c.cb = -1;
+        return c.ca >= 0 && e.valid[c.ca];
     }
     c.op = op;
-    c.ca = raw2c[a];
+    c.ca = e.raw2c[a];
+    if (rung == 3 && e.stream3) {
+        if (!e.r2_valid[b - e.sd.off[2]] || c.ca < 0 || !e.valid[c.ca]) return false;
+        int r2, o2;
+        int64_t k, l;
+        decode_id(e.sd, b, r2, o2, k, l);
+        c.kind = 3; c.cb = -1; c.op2 = o2; c.cc = e.raw2c[k]; c.cd = l >= 0 ? e.raw2c[l] : -1;
+        return c.cc >= 0;
+    }
     if (b < 0) {
         c.kind = 1; c.cb = -1;
-        return c.ca >= 0;
+        return c.ca >= 0 && e.valid[c.ca];
     }
     c.kind = 2;
-    c.cb = raw2c[b];
-    return c.ca >= 0 && c.cb >= 0;
+    c.cb = e.raw2c[b];
+    return c.ca >= 0 && c.cb >= 0 && e.valid[c.ca] && e.valid[c.cb];
 }
 
 // Exact two-pass Pearson of one candidate against T centered targets by one
@@ -222,16 +266,32 @@ __device__ __forceinline__ bool cand_of_id(const SpaceDev& sd, int streamed,
 template <int TMAX>
 __device__ bool wave_exact_r(const Cand& c, const Ops& o, int n, int T,
                              const double* __restrict__ Yc, const double* __restrict__ syy,
-                             double* r) {
+                             double* r, double* mean_out = nullptr, double* msq_out = nullptr) {
     const int lane = threadIdx.x & 63;
     double s = 0.0;
     int bad = 0;
+    const bool addsub = (c.kind == 2 || c.kind == 3) && (c.op == OP_ADD || c.op == OP_SUB);
+    double ff = 0.0, ab = 0.0;
     for (int i = lane; i < n; i += 64) {
         const double f = cand_value(c, o, i);
         bad |= !isfinite(f);
         s += f;
+        if (addsub) {
+            const double a = o.Vf[(int64_t)c.ca * o.ldn + i];
+            double b;
+            if (c.kind == 2) b = o.Vf[(int64_t)c.cb * o.ldn + i];
+            else b = c.cd < 0 ? unary_value(c.op2, o, c.cc, i)
+                              : apply_op(c.op2, o.Vf[(int64_t)c.cc * o.ldn + i], o.Vf[(int64_t)c.cd * o.ldn + i]);
+            ff += f * f;
+            ab += a * a + b * b;
+        }
     }
     if (__any(bad)) return false;
+    if (addsub) {                                   // cancellation to rounding noise
+        ff = wave_sum(ff);
+        ab = wave_sum(ab);
+        if (ff <= TAU_CANCEL * TAU_CANCEL * ab) return false;
+    }
     const double m = wave_sum(s) / n;
     double sxx = 0.0, sxy[TMAX];
 #pragma unroll
@@ -250,6 +310,8 @@ __device__ bool wave_exact_r(const Cand& c, const Ops& o, int n, int T,
 #pragma unroll
     for (int t = 0; t < TMAX; t++)
         if (t < T) r[t] = wave_sum(sxy[t]) / sqrt(sxx * syy[t]);
+    if (mean_out) *mean_out = m;
+    if (msq_out) *msq_out = sxx / n + m * m;
     return true;
 }
 
@@ -266,21 +328,28 @@ __global__ __launch_bounds__(256) void k_score_list(const ListItem* __restrict__
                                                     const double* __restrict__ Yc,
                                                     const double* __restrict__ syy, int64_t N,
                                                     double* __restrict__ scores,
-                                                    unsigned long long* __restrict__ nscored) {
+                                                    unsigned long long* __restrict__ nscored,
+                                                    uint8_t* __restrict__ r2v, double* __restrict__ r2m,
+                                                    double* __restrict__ r2q, int64_t off2, int64_t off3) {
     const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (w >= m) return;
     const ListItem it = items[w];
-    Cand c{it.kind, it.op, it.ca, it.cb};
+    Cand c{it.kind, it.op, it.ca, it.cb, OP_NONE, -1, -1};
     bool ok = valid[c.ca] && (c.kind < 2 || valid[c.cb]);
     if (c.kind == 0) ok = valid[c.ca];
-    double r[DISCOVER_MAX_TARGETS];
-    ok = ok && wave_exact_r<DISCOVER_MAX_TARGETS>(c, o, n, T, Yc, syy, r);
+    double r[DISCOVER_MAX_TARGETS], mean = 0.0, msq = 0.0;
+    ok = ok && wave_exact_r<DISCOVER_MAX_TARGETS>(c, o, n, T, Yc, syy, r, &mean, &msq);
     if ((threadIdx.x & 63) == 0) {
         if (!ok) {
             for (int t = 0; t < (mode ? 1 : T); t++) scores[(int64_t)t * N + it.id] = __longlong_as_double(-1LL);
             return;
         }
         atomicAdd(nscored, 1ull);
+        if (r2v && it.id >= off2 && it.id < off3) {
+            r2v[it.id - off2] = 1;
+            r2m[it.id - off2] = mean;
+            r2q[it.id - off2] = msq;
+        }
         if (mode == DISCOVER_SCORE_MAX) {
             double mx = 0.0;
             for (int t = 0; t < T; t++) mx = fmax(mx, fabs(r[t]));
@@ -320,6 +389,10 @@ struct PairArgs {
     int64_t* fix_ids;         // candidates whose shifted moments are ill-conditioned
     unsigned long long* fix_cnt;
     int64_t fix_cap;
+    uint8_t* r2v;             // rung-2 operand statistics for a streamed rung 3 (or NULL)
+    double* r2m;
+    double* r2q;
+    const double* msq;        // mean square of every operand feature
 };
 
 // One block = one tile; its 4 waves take consecutive quarters of the samples
@@ -455,7 +528,14 @@ __global__ __launch_bounds__(256) void k_screen_pairs(PairArgs g) {
                 for (int t = 0; t < (g.mode ? 1 : g.T); t++) g.scores[(int64_t)t * g.N + id] = nanv;
                 continue;
             }
-            const double kappa = varn > 0.0 ? S2v / varn : INFINITY;
+            double kappa = varn > 0.0 ? S2v / varn : INFINITY;
+            if (o < 2) {
+                // a sum or difference that may have cancelled to rounding noise
+                // is decided exactly as well
+                const double c0 = o == 0 ? mua + mub : mua - mub;
+                const double ff = S2v + 2.0 * c0 * S1v + nn * c0 * c0;
+                if (ff <= 1e-12 * nn * (g.msq[ic] + g.msq[jc[jj]])) kappa = INFINITY;
+            }
             if (!(kappa <= KAPPA_MAX)) {
                 // the shift was far from the mean: decide exactly in the fix-up pass
                 const unsigned long long slot = atomicAdd(g.fix_cnt, 1ull);
@@ -484,6 +564,11 @@ __global__ __launch_bounds__(256) void k_screen_pairs(PairArgs g) {
             const double err = 4.0 * nn * EPS64 * kappa;
             const bool precise = kappa <= KAPPA_MAX;
             cnt++;
+            if (g.r2v && precise) {
+                g.r2v[id - g.sd.off[2]] = 1;
+                g.r2m[id - g.sd.off[2]] = mean;
+                g.r2q[id - g.sd.off[2]] = varn / nn + mean * mean;
+            }
             if (g.mode == DISCOVER_SCORE_MAX) {
                 g.scores[id] = precise ? best : -(best + err);
             } else {
@@ -503,6 +588,488 @@ __global__ __launch_bounds__(256) void k_screen_pairs(PairArgs g) {
 #undef S1
 #undef S2
 #undef DT
+}
+
+// ---------------------------------------------- operator-limited rung 3
+// Candidates op3(f_i, f_j2): i in the materialised partner pool (uniform
+// across the wave), j2 a rung-2 feature regenerated on the fly in every lane
+// from two rung-1 operands (never stored).  The wave's 64 rung-2 features
+// come from one rung-2 tile: (op2, l, 64 consecutive k) for binary op2,
+// (op2, 64 consecutive l) for unary op2, or a same-unit partner list.
+// Shifts: add/sub use centered operands, mul mu_i mu_j2, div mu_i / mu_j2,
+// rdiv mu_j2 / mu_i-type estimates (mu_j2 from the rung-2 screening pass).
+struct R3Args {
+    const int4* tiles;        // (op2, l or l0, k0 or list offset, -1 dense | count | -2 unary)
+    const int32_t* klist;
+    int64_t n_tiles;
+    int n, ldm, ldn, Mc, c1_lo, c1_hi, pe, B;
+    const double *Vs, *Rs, *Cs, *Vf, *Rf, *Cf, *mu, *mur;
+    const uint8_t* valid;
+    const int64_t* mat_raw;
+    const int32_t* mat_unit;
+    const uint8_t* r2v;
+    const double* r2m;
+    const double* r2q;
+    const double* msq;
+    const double* Yn;
+    const double* ysum;
+    int T, mode;
+    uint32_t opmask;          // rung-3 binary operators (bits 0..4 = add..rdiv)
+    SpaceDev sd;
+    int64_t N;
+    double* scores;
+    unsigned long long* nscored;
+    int64_t* fix_ids;
+    unsigned long long* fix_cnt;
+    int64_t fix_cap;
+};
+
+__device__ __forceinline__ bool dev_unit_rule(int op, int B, const int32_t* ua, const int32_t* ub,
+                                              int32_t* out) {
+    switch (op) {
+    case OP_EXP: case OP_LOG:
+        for (int k = 0; k < B; k++) if (ua[k]) return false;
+        for (int k = 0; k < B; k++) out[k] = 0;
+        return true;
+    case OP_SQRT:
+        for (int k = 0; k < B; k++) if (ua[k] & 1) return false;
+        for (int k = 0; k < B; k++) out[k] = ua[k] / 2;
+        return true;
+    case OP_SQ: for (int k = 0; k < B; k++) out[k] = 2 * ua[k]; return true;
+    case OP_INV: for (int k = 0; k < B; k++) out[k] = -ua[k]; return true;
+    case OP_ADD: case OP_SUB:
+        for (int k = 0; k < B; k++) if (ua[k] != ub[k]) return false;
+        for (int k = 0; k < B; k++) out[k] = ua[k];
+        return true;
+    case OP_MUL: for (int k = 0; k < B; k++) out[k] = ua[k] + ub[k]; return true;
+    case OP_DIV: for (int k = 0; k < B; k++) out[k] = ua[k] - ub[k]; return true;
+    default: for (int k = 0; k < B; k++) out[k] = ub[k] - ua[k]; return true;
+    }
+}
+
+template <int OPS, int IC, int TP>
+__global__ __launch_bounds__(256) void k_screen_r3(R3Args g) {
+    constexpr int NOP = ((OPS >> 0) & 1) + ((OPS >> 1) & 1) + ((OPS >> 2) & 1) +
+                        ((OPS >> 3) & 1) + ((OPS >> 4) & 1);
+    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (w >= g.n_tiles) return;
+    const int lane = threadIdx.x & 63;
+    const int4 tile = g.tiles[w];
+    const int op2 = tile.x;
+    // this lane's rung-2 feature: operands (k, l) compact, raw id j2
+    int k = -1, l = -1;
+    bool lok;
+    if (tile.w == -2) {                                   // unary op2 over 64 consecutive l
+        l = tile.y + lane;
+        lok = l < g.c1_hi;
+    } else if (tile.w == -1) {                            // binary op2, k = k0 + lane < l
+        l = tile.y;
+        k = tile.z + lane;
+        lok = k < l;
+    } else {                                              // binary op2, explicit partner list
+        l = tile.y;
+        lok = lane < tile.w;
+        k = g.klist[tile.z + (lok ? lane : 0)];
+    }
+    const int lc = lok ? l : g.c1_lo;
+    const int kc = (k >= 0 && lok) ? k : 0;
+    int64_t j2 = 0;
+    if (lok) j2 = tile.w == -2 ? unary_id(g.sd, 2, op2, g.mat_raw[lc])
+                              : pair_id(g.sd, 2, op2, g.mat_raw[kc], g.mat_raw[lc]);
+    const int64_t o2 = j2 - g.sd.off[2];
+    const bool ok2 = lok && g.r2v[o2];
+    const double mu2 = ok2 ? g.r2m[o2] : 1.0;
+    const double q2 = ok2 ? g.r2q[o2] : 1.0;
+    int32_t u2[DISCOVER_MAX_UNITS];
+    if (g.B > 0) {
+        bool leg = dev_unit_rule(op2, g.B, g.mat_unit + (int64_t)(tile.w == -2 ? lc : kc) * g.B,
+                                 g.mat_unit + (int64_t)lc * g.B, u2);
+        (void)leg;                                        // ok2 already implies legality
+    }
+    const bool want_rcp = (OPS & 8) != 0;
+    const int nn_i = g.n;
+    const double nn = (double)g.n;
+    unsigned cnt = 0;
+    for (int i0 = 0; i0 < g.pe; i0 += IC) {
+        // per-lane legality of add/sub partners (unit exponents must agree)
+        bool addok[IC];
+        bool any_add = false;
+#pragma unroll
+        for (int ii = 0; ii < IC; ii++) {
+            const int i = min(i0 + ii, g.pe - 1);
+            bool eq = true;
+            for (int b = 0; b < g.B; b++) eq = eq && (g.mat_unit[(int64_t)i * g.B + b] == u2[b]);
+            addok[ii] = ok2 && (i0 + ii < g.pe) && eq;
+            any_add |= addok[ii];
+        }
+        const bool wave_add = (OPS & 3) && __any(any_add);
+        double sh[IC][NOP];
+#pragma unroll
+        for (int ii = 0; ii < IC; ii++) {
+            const int i = min(i0 + ii, g.pe - 1);
+            const double mi = g.mu[i], mri = g.mur[i];
+            int q = 0;
+            if (OPS & 1) sh[ii][q++] = 0.0;
+            if (OPS & 2) sh[ii][q++] = 0.0;
+            if (OPS & 4) sh[ii][q++] = mi * mu2;
+            if (OPS & 8) sh[ii][q++] = mu2 != 0.0 ? mi / mu2 : 0.0;
+            if (OPS & 16) sh[ii][q++] = mu2 * mri;
+        }
+        double acc[IC][NOP][2 + TP];
+#pragma unroll
+        for (int ii = 0; ii < IC; ii++)
+#pragma unroll
+            for (int q = 0; q < NOP; q++)
+#pragma unroll
+                for (int v = 0; v < 2 + TP; v++) acc[ii][q][v] = 0.0;
+        for (int s = 0; s < nn_i; s++) {
+            double f2;
+            if (tile.w == -2) {
+                const int64_t so = (int64_t)s * g.ldm + lc;
+                const double a = g.Vs[so];
+                f2 = op2 == OP_INV ? g.Rs[so] : op2 == OP_SQ ? a * a : apply_op(op2, a, 0.0);
+            } else {
+                const double a = g.Vs[(int64_t)s * g.ldm + kc];
+                const double b = g.Vf[(int64_t)lc * g.ldn + s];
+                switch (op2) {
+                case OP_ADD: f2 = a + b; break;
+                case OP_SUB: f2 = a - b; break;
+                case OP_MUL: f2 = a * b; break;
+                case OP_DIV: f2 = a * g.Rf[(int64_t)lc * g.ldn + s]; break;
+                default: f2 = b * g.Rs[(int64_t)s * g.ldm + kc]; break;
+                }
+            }
+            const double f2c = f2 - mu2;
+            double rf2 = 0.0;
+            if (want_rcp) {
+                double r = __builtin_amdgcn_rcp(f2);
+                r = fma(r, fma(-f2, r, 1.0), r);
+                rf2 = fma(r, fma(-f2, r, 1.0), r);
+            }
+            double y[TP];
+#pragma unroll
+            for (int t = 0; t < TP; t++) y[t] = g.Yn[(int64_t)t * g.ldn + s];
+#pragma unroll
+            for (int ii = 0; ii < IC; ii++) {
+                const int i = min(i0 + ii, g.pe - 1);
+                const double x = g.Vf[(int64_t)i * g.ldn + s];
+                const double xc = (OPS & 3) ? g.Cf[(int64_t)i * g.ldn + s] : 0.0;
+                const double rx = (OPS & 16) ? g.Rf[(int64_t)i * g.ldn + s] : 0.0;
+                double f[NOP];
+                int q = 0;
+                if (OPS & 1) { f[q] = xc + f2c; q++; }
+                if (OPS & 2) { f[q] = xc - f2c; q++; }
+                if (OPS & 4) { f[q] = fma(x, f2, -sh[ii][q]); q++; }
+                if (OPS & 8) { f[q] = fma(x, rf2, -sh[ii][q]); q++; }
+                if (OPS & 16) { f[q] = fma(f2, rx, -sh[ii][q]); q++; }
+#pragma unroll
+                for (int qq = 0; qq < NOP; qq++) {
+                    if (qq < ((OPS & 1) + ((OPS >> 1) & 1)) && !wave_add) continue;   // uniform
+                    acc[ii][qq][0] += f[qq];
+                    acc[ii][qq][1] = fma(f[qq], f[qq], acc[ii][qq][1]);
+#pragma unroll
+                    for (int t = 0; t < TP; t++) acc[ii][qq][2 + t] = fma(f[qq], y[t], acc[ii][qq][2 + t]);
+                }
+            }
+        }
+        // finalise the IC x NOP candidates of this chunk
+#pragma unroll
+        for (int ii = 0; ii < IC; ii++) {
+            const int i = i0 + ii;
+            if (i >= g.pe) continue;
+            int q = 0;
+#pragma unroll
+            for (int o = 0; o < 5; o++) {
+                if (!((OPS >> o) & 1)) continue;
+                const int qq = q++;
+                // score slots start as NaN: unit-illegal or invalid candidates are
+                // simply not written
+                if (!((g.opmask >> o) & 1) || !ok2 || !g.valid[i]) continue;
+                if (o < 2 && !addok[ii]) continue;
+                const int64_t id = pair_id(g.sd, 3, OP_ADD + o, g.mat_raw[i], j2);
+                const double nanv = __longlong_as_double(-1LL);
+                const double S1v = acc[ii][qq][0], S2v = acc[ii][qq][1];
+                const double m1 = S1v / nn, varn = S2v - S1v * m1;
+                if (!(S2v < INFINITY) || !(fabs(S1v) < INFINITY)) continue;
+                double kappa = varn > 0.0 ? S2v / varn : INFINITY;
+                if (o < 2) {                                      // possible cancellation
+                    const double c0 = o == 0 ? g.mu[i] + mu2 : g.mu[i] - mu2;
+                    const double ff = S2v + 2.0 * c0 * S1v + nn * c0 * c0;
+                    if (ff <= 1e-12 * nn * (g.msq[i] + q2)) kappa = INFINITY;
+                }
+                if (!(kappa <= KAPPA_MAX)) {
+                    const unsigned long long slot = atomicAdd(g.fix_cnt, 1ull);
+                    if ((int64_t)slot < g.fix_cap) {
+                        g.fix_ids[slot] = id;
+                        for (int t = 0; t < (g.mode ? 1 : g.T); t++) g.scores[(int64_t)t * g.N + id] = nanv;
+                        continue;
+                    }
+                }
+                double shift = sh[ii][qq];
+                if (o == 0) shift = g.mu[i] + mu2;
+                if (o == 1) shift = g.mu[i] - mu2;
+                const double mean = shift + m1;
+                const bool nonconst = varn / nn > TAU_CONST * TAU_CONST * (varn / nn + mean * mean);
+                if (kappa <= KAPPA_MAX && !nonconst) {
+                    for (int t = 0; t < (g.mode ? 1 : g.T); t++) g.scores[(int64_t)t * g.N + id] = nanv;
+                    continue;
+                }
+                const double isd = 1.0 / sqrt(varn);
+                double out[TP], best = 0.0;
+#pragma unroll
+                for (int t = 0; t < TP; t++) {
+                    out[t] = fabs((acc[ii][qq][2 + t] - S1v * g.ysum[t] / nn) * isd);
+                    if (t < g.T) best = fmax(best, out[t]);
+                }
+                const double err = 4.0 * nn * EPS64 * kappa;
+                const bool precise = kappa <= KAPPA_MAX;
+                cnt++;
+                if (g.mode == DISCOVER_SCORE_MAX) {
+                    g.scores[id] = precise ? best : -(best + err);
+                } else {
+#pragma unroll
+                    for (int t = 0; t < TP; t++)
+                        if (t < g.T) g.scores[(int64_t)t * g.N + id] = precise ? out[t] : -(out[t] + err);
+                }
+            }
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor((int)cnt, o, 64);
+    if (lane == 0 && cnt) atomicAdd(g.nscored, (unsigned long long)cnt);
+}
+
+// -------------------------------------------- reduced-precision screen
+// SIS for many targets at once as a BF16/FP16 MFMA product with FP32
+// accumulation over standardised values (the precision form).  Pass 1 gives
+// each candidate's mean and standard deviation in FP64 (shifted moments as
+// in the FP64 kernel); pass 2 forms z = (f - mean) / sd in FP64, rounds it
+// to BF16/FP16 and multiplies it with the standardised targets on the
+// matrix cores: r_t = sum_s zy[t][s] z[s] / n.
+//
+// MFMA v_mfma_f32_16x16x32_{bf16,f16}: A = targets (16 rows x 32 samples),
+// B = candidates (32 samples x 16 columns), D (16 x 16, FP32).  Lane l
+// supplies A[l%16][8(l/16)..+7] and B[8(l/16)..+7][l%16] and receives
+// D[4(l/16)+e][l%16], e = 0..3.  So lane l evaluates candidate l%16 of each
+// 16-wide group at samples 8(l/16)..+7 of every 32-sample chunk: the B
+// operand is built in registers, no LDS staging.
+//
+// Error bound (guard half-width): standardised vectors have sum z^2 = n, so
+// |r_lp - r| <= 2u + u^2 + gamma_n(FP32) (+2^-24 for FP16 subnormals), with
+// u = 2^-8 (BF16) or 2^-11 (FP16); every candidate within 2 delta of the
+// pool threshold is rescored in FP64.
+constexpr int LP_IB = 1;
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8_t;
+typedef __attribute__((ext_vector_type(8))) _Float16 f16x8_t;
+typedef __attribute__((ext_vector_type(4))) float f32x4_t;
+
+template <bool FP16>
+struct LpVec;
+template <>
+struct LpVec<false> {
+    typedef bf16x8_t T;
+    static __device__ __forceinline__ __bf16 cvt(float x) { return (__bf16)x; }
+    static __device__ __forceinline__ f32x4_t mma(T a, T b, f32x4_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+};
+template <>
+struct LpVec<true> {
+    typedef f16x8_t T;
+    static __device__ __forceinline__ _Float16 cvt(float x) { return (_Float16)x; }
+    static __device__ __forceinline__ f32x4_t mma(T a, T b, f32x4_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+    }
+};
+
+// Standardised targets in low precision: Ylp[t][s] = Yn[t][s] * sqrt(n)
+// for t < T, 0 for padding rows and samples >= n.  ldl = n rounded to 32.
+template <bool FP16>
+__global__ void k_targets_lp(int n, int T, int ldn, int ldl, const double* __restrict__ Yn,
+                             typename std::conditional<FP16, _Float16, __bf16>::type* __restrict__ Ylp) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = blockIdx.y;
+    if (s >= ldl) return;
+    const double v = (t < T && s < n) ? Yn[(int64_t)t * ldn + s] * sqrt((double)n) : 0.0;
+    Ylp[(int64_t)t * ldl + s] = LpVec<FP16>::cvt((float)v);
+}
+
+template <int OPS, bool FP16>
+__global__ __launch_bounds__(256) void k_screen_lp(PairArgs g, const void* __restrict__ Ylp_, int ldl) {
+    constexpr int NOP = ((OPS >> 0) & 1) + ((OPS >> 1) & 1) + ((OPS >> 2) & 1) +
+                        ((OPS >> 3) & 1) + ((OPS >> 4) & 1);
+    constexpr int IB = LP_IB;                              // LP_IB x 16 operand features i per wave
+    constexpr int G = IB * NOP;
+    typedef typename LpVec<FP16>::T VT;
+    typedef typename std::conditional<FP16, _Float16, __bf16>::type ET;
+    const ET* __restrict__ Ylp = (const ET*)Ylp_;
+    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (w >= g.n_tiles) return;
+    const int lane = threadIdx.x & 63;
+    const int col = lane & 15, kb = lane >> 4;
+    const int2 tile = g.tiles[w];
+    const int jc = tile.x;                                 // one j per tile
+    const double mub = g.mu[jc], murb = g.mur[jc];
+    int ic[IB];
+    bool iok[IB];
+    double sh[IB][NOP];
+#pragma unroll
+    for (int b = 0; b < IB; b++) {
+        const int i = tile.y + 16 * b + col;
+        iok[b] = i < g.i_end && i < jc;
+        ic[b] = i < g.Mc ? i : 0;
+        const double mua = g.mu[ic[b]], mura = g.mur[ic[b]];
+        int k = 0;
+        if (OPS & 1) sh[b][k++] = 0.0;
+        if (OPS & 2) sh[b][k++] = 0.0;
+        if (OPS & 4) sh[b][k++] = mua * mub;
+        if (OPS & 8) sh[b][k++] = mua * murb;
+        if (OPS & 16) sh[b][k++] = mura * mub;
+    }
+    auto values = [&](int s, double f[IB][NOP]) {
+        const double b_ = g.Vf[(int64_t)jc * g.ldn + s];
+        const double rb = g.Rf[(int64_t)jc * g.ldn + s];
+        const double bc = g.Cf[(int64_t)jc * g.ldn + s];
+#pragma unroll
+        for (int b = 0; b < IB; b++) {
+            const int64_t so = (int64_t)s * g.ldm + ic[b];
+            const double a = g.Vs[so], ra = g.Rs[so], ac = g.Cs[so];
+            int k = 0;
+            if (OPS & 1) { f[b][k] = ac + bc; k++; }
+            if (OPS & 2) { f[b][k] = ac - bc; k++; }
+            if (OPS & 4) { f[b][k] = fma(a, b_, -sh[b][k]); k++; }
+            if (OPS & 8) { f[b][k] = fma(a, rb, -sh[b][k]); k++; }
+            if (OPS & 16) { f[b][k] = fma(ra, b_, -sh[b][k]); k++; }
+        }
+    };
+    // pass 1: shifted moments over this lane's samples, then across the 4
+    // lanes that share a candidate
+    double s1[G], s2[G];
+#pragma unroll
+    for (int q = 0; q < G; q++) { s1[q] = 0.0; s2[q] = 0.0; }
+    const int nch = (g.n + 31) / 32;
+    for (int c = 0; c < nch; c++) {
+        for (int e = 0; e < 8; e++) {
+            const int s = 32 * c + 8 * kb + e;
+            if (s >= g.n) break;
+            double f[IB][NOP];
+            values(s, f);
+#pragma unroll
+            for (int b = 0; b < IB; b++)
+#pragma unroll
+                for (int k = 0; k < NOP; k++) {
+                    s1[b * NOP + k] += f[b][k];
+                    s2[b * NOP + k] = fma(f[b][k], f[b][k], s2[b * NOP + k]);
+                }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < G; q++) {
+        // fixed order: (kb0 + kb1) + (kb2 + kb3) in every lane
+        const double a1 = s1[q] + __shfl_xor(s1[q], 16, 64);
+        s1[q] = a1 + __shfl_xor(a1, 32, 64);
+        const double a2 = s2[q] + __shfl_xor(s2[q], 16, 64);
+        s2[q] = a2 + __shfl_xor(a2, 32, 64);
+    }
+    const double nn = (double)g.n;
+    double isd[G], cz[G];
+    unsigned okmask = 0, fixmask = 0;
+#pragma unroll
+    for (int b = 0; b < IB; b++)
+#pragma unroll
+        for (int k = 0; k < NOP; k++) {
+            const int q = b * NOP + k;
+            const double m1 = s1[q] / nn, varn = s2[q] - s1[q] * m1;
+            const bool fin = (s2[q] < INFINITY) && (fabs(s1[q]) < INFINITY);
+            double kappa = varn > 0.0 ? s2[q] / varn : INFINITY;
+            if ((OPS & 3) && k < ((OPS & 1) + ((OPS >> 1) & 1))) {   // add / sub
+                const bool isadd = (OPS & 1) && k == 0;
+                const double c0 = isadd ? g.mu[ic[b]] + mub : g.mu[ic[b]] - mub;
+                const double ff = s2[q] + 2.0 * c0 * s1[q] + nn * c0 * c0;
+                if (ff <= 1e-12 * nn * (g.msq[ic[b]] + g.msq[jc])) kappa = INFINITY;
+            }
+            bool ok = iok[b] && g.valid[ic[b]] && g.valid[jc] && fin;
+            if (ok && !(kappa <= KAPPA_MAX)) { fixmask |= 1u << q; ok = false; }
+            isd[q] = ok ? sqrt(nn / varn) : 0.0;           // 1 / population sd
+            cz[q] = m1 * isd[q];
+            if (ok) okmask |= 1u << q;
+        }
+    // pass 2: low-precision products on the matrix cores
+    f32x4_t acc[G];
+#pragma unroll
+    for (int q = 0; q < G; q++) acc[q] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    for (int c = 0; c < nch; c++) {
+        const VT ya = *(const VT*)(Ylp + (int64_t)col * ldl + 32 * c + 8 * kb);
+        VT bv[G];
+#pragma unroll
+        for (int e = 0; e < 8; e++) {
+            const int s = 32 * c + 8 * kb + e;
+            double f[IB][NOP];
+            if (s < g.n) values(s, f);
+#pragma unroll
+            for (int q = 0; q < G; q++) {
+                const double z = s < g.n ? fma(f[q / NOP][q % NOP], isd[q], -cz[q]) : 0.0;
+                bv[q][e] = LpVec<FP16>::cvt((float)z);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < G; q++) acc[q] = LpVec<FP16>::mma(ya, bv[q], acc[q]);
+    }
+    // scores: lane holds r for targets 4kb..4kb+3 of candidate col
+    unsigned cnt = 0;
+#pragma unroll
+    for (int b = 0; b < IB; b++) {
+        const int i = tile.y + 16 * b + col;
+        int k = 0;
+#pragma unroll
+        for (int o = 0; o < 5; o++) {
+            if (!((OPS >> o) & 1)) continue;
+            const int q = b * NOP + k++;
+            double r[4];
+            double mx = 0.0;
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                r[e] = fabs((double)acc[q][e]) / nn;
+                if (4 * kb + e < g.T) mx = fmax(mx, r[e]);
+            }
+            mx = fmax(mx, __shfl_xor(mx, 16, 64));
+            mx = fmax(mx, __shfl_xor(mx, 32, 64));
+            if (!iok[b] || !((g.opmask >> o) & 1)) continue;
+            const int64_t id = pair_id(g.sd, g.r, OP_ADD + o, g.mat_raw[ic[b]], g.mat_raw[jc]);
+            const double nanv = __longlong_as_double(-1LL);
+            const bool ok = (okmask >> q) & 1;
+            if ((fixmask >> q) & 1) {
+                if (kb == 0) {
+                    const unsigned long long slot = atomicAdd(g.fix_cnt, 1ull);
+                    if ((int64_t)slot < g.fix_cap) g.fix_ids[slot] = id;
+                    if (g.mode == DISCOVER_SCORE_MAX) g.scores[id] = nanv;
+                }
+                if (g.mode != DISCOVER_SCORE_MAX)
+                    for (int e = 0; e < 4; e++)
+                        if (4 * kb + e < g.T) g.scores[(int64_t)(4 * kb + e) * g.N + id] = nanv;
+                continue;
+            }
+            if (g.r2v && ok && kb == 0) {
+                const double sh_ = (o == 0) ? g.mu[ic[b]] + mub : (o == 1) ? g.mu[ic[b]] - mub : sh[b][k - 1];
+                const double mean_ = sh_ + s1[q] / nn;
+                const double var_ = (s2[q] - s1[q] * s1[q] / nn) / nn;
+                g.r2v[id - g.sd.off[2]] = 1;
+                g.r2m[id - g.sd.off[2]] = mean_;
+                g.r2q[id - g.sd.off[2]] = var_ + mean_ * mean_;
+            }
+            if (g.mode == DISCOVER_SCORE_MAX) {
+                if (kb == 0) {
+                    g.scores[id] = ok ? mx : nanv;
+                    cnt += ok;
+                }
+            } else {
+                for (int e = 0; e < 4; e++)
+                    if (4 * kb + e < g.T) g.scores[(int64_t)(4 * kb + e) * g.N + id] = ok ? r[e] : nanv;
+                if (kb == 0) cnt += ok;
+            }
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor((int)cnt, o, 64);
+    if (lane == 0 && cnt) atomicAdd(g.nscored, (unsigned long long)cnt);
 }
 
 // ------------------------------------------------------------ selection
@@ -529,22 +1096,21 @@ __global__ __launch_bounds__(256) void k_compact(const double* __restrict__ sc, 
 template <int TMAX>
 __global__ __launch_bounds__(256) void k_rescore(const int64_t* __restrict__ pool,
                                                  const unsigned long long* __restrict__ Pp, int64_t cap,
-                                                 SpaceDev sd, int streamed,
-                                                 const int32_t* __restrict__ raw2c,
-                                                 const uint8_t* __restrict__ valid, Ops o, int n,
+                                                 EvalCtx ev, Ops o, int n,
                                                  int T, int mode, int tlist,
                                                  const double* __restrict__ Yc,
                                                  const double* __restrict__ syy,
                                                  const int64_t* __restrict__ excl, int n_excl,
                                                  double* __restrict__ ps,
-                                                 uint8_t* __restrict__ pex) {
+                                                 uint8_t* __restrict__ pex,
+                                                 const double* __restrict__ sc_row,
+                                                 unsigned long long* __restrict__ maxerr) {
     const int64_t P = min((int64_t)*Pp, cap);
     const int lane = threadIdx.x & 63;
     for (int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); w < P; w += (int64_t)gridDim.x * 4) {
     const int64_t id = pool[w];
     Cand c;
-    bool ok = cand_of_id(sd, streamed, raw2c, id, c);
-    ok = ok && valid[c.ca] && (c.kind < 2 || valid[c.cb]);
+    bool ok = cand_of_id(ev, id, c);
     double r[TMAX];
     ok = ok && wave_exact_r<TMAX>(c, o, n, T, Yc, syy, r);
     int ex = 0;
@@ -563,6 +1129,9 @@ __global__ __launch_bounds__(256) void k_rescore(const int64_t* __restrict__ poo
         }
         ps[w] = s;
         pex[w] = (uint8_t)ex;
+        const double x = sc_row[id];                      // screening-pass score
+        if (s > 0.0 && x > 0.0)
+            atomicMax(maxerr, (unsigned long long)__double_as_longlong(fabs(x - s)));
     }
     }
 }
@@ -572,23 +1141,27 @@ __global__ __launch_bounds__(256) void k_rescore(const int64_t* __restrict__ poo
 template <int TMAX>
 __global__ __launch_bounds__(256) void k_fixup(const int64_t* __restrict__ ids,
                                                const unsigned long long* __restrict__ cnt,
-                                               int64_t cap, SpaceDev sd, int streamed,
-                                               const int32_t* __restrict__ raw2c,
-                                               const uint8_t* __restrict__ valid, Ops o, int n,
+                                               int64_t cap, EvalCtx ev, Ops o, int n,
                                                int T, int mode, const double* __restrict__ Yc,
                                                const double* __restrict__ syy, int64_t N,
                                                double* __restrict__ scores,
-                                               unsigned long long* __restrict__ nscored) {
+                                               unsigned long long* __restrict__ nscored,
+                                               uint8_t* __restrict__ r2v, double* __restrict__ r2m,
+                                               double* __restrict__ r2q) {
     const int64_t m = min((int64_t)*cnt, cap);
     for (int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); w < m; w += (int64_t)gridDim.x * 4) {
         const int64_t id = ids[w];
         Cand c;
-        bool ok = cand_of_id(sd, streamed, raw2c, id, c);
-        ok = ok && valid[c.ca] && (c.kind < 2 || valid[c.cb]);
-        double r[TMAX];
-        ok = ok && wave_exact_r<TMAX>(c, o, n, T, Yc, syy, r);
+        bool ok = cand_of_id(ev, id, c);
+        double r[TMAX], mean = 0.0, msq = 0.0;
+        ok = ok && wave_exact_r<TMAX>(c, o, n, T, Yc, syy, r, &mean, &msq);
         if ((threadIdx.x & 63) != 0 || !ok) continue;
         atomicAdd(nscored, 1ull);
+        if (r2v && id >= ev.sd.off[2] && id < ev.sd.off[3]) {     // rung-2 operand statistics
+            r2v[id - ev.sd.off[2]] = 1;
+            r2m[id - ev.sd.off[2]] = mean;
+            r2q[id - ev.sd.off[2]] = msq;
+        }
         if (mode == DISCOVER_SCORE_MAX) {
             double mx = 0.0;
             for (int t = 0; t < T; t++) mx = fmax(mx, fabs(r[t]));
@@ -682,8 +1255,7 @@ __global__ __launch_bounds__(256) void k_pairs(const int64_t* __restrict__ pool,
                                                const int32_t* __restrict__ lo,
                                                const int64_t* __restrict__ off,
                                                const unsigned long long* __restrict__ Pp, int64_t cap,
-                                               SpaceDev sd, int streamed,
-                                               const int32_t* __restrict__ raw2c, Ops o, int n,
+                                               EvalCtx ev, Ops o, int n,
                                                uint8_t* __restrict__ flag, int64_t flag_cap) {
     const int64_t P = min((int64_t)*Pp, cap);
     const int64_t total = min(off[P], flag_cap);
@@ -699,8 +1271,7 @@ __global__ __launch_bounds__(256) void k_pairs(const int64_t* __restrict__ pool,
     const int64_t q = a;
     const int64_t pe = lo[q] + (w - off[q]);
     Cand cu, cv;
-    const bool okp = cand_of_id(sd, streamed, raw2c, pool[order[pe]], cu) &&
-                     cand_of_id(sd, streamed, raw2c, pool[order[q]], cv);
+    const bool okp = cand_of_id(ev, pool[order[pe]], cu) && cand_of_id(ev, pool[order[q]], cv);
     if (!okp) {
         if (lane == 0) flag[w] = 0;
         continue;
@@ -839,20 +1410,37 @@ __global__ __launch_bounds__(GRP_THREADS) void k_groups(
     (void)merged;
     __syncthreads();
     const int64_t ns = min((int64_t)k, nunb);
-    // 5. representatives in (-score, ID) order (rank sort of <= k entries)
-    for (int64_t i = t; i < ns; i += GRP_THREADS) {
-        const int32_t rp = reppos[headpos[i]];
-        const double si = ps[order[rp]];
-        const int64_t ii = pool[order[rp]];
-        int64_t rank = 0;
-        for (int64_t j = 0; j < ns; j++) {
-            const int32_t rq = reppos[headpos[j]];
-            const double sj = ps[order[rq]];
-            const int64_t ij = pool[order[rq]];
-            rank += (sj > si) || (sj == si && ij < ii);
+    // 5. representatives in (-score, ID) order (rank sort of <= k entries,
+    // staged through LDS in tiles)
+    __shared__ double tsc[GRP_THREADS];
+    __shared__ int64_t tid_[GRP_THREADS];
+    for (int64_t i0 = 0; i0 < ns; i0 += GRP_THREADS) {
+        const int64_t i = i0 + t;
+        double si = 0.0;
+        int64_t ii = 0;
+        if (i < ns) {
+            const int32_t rp = reppos[headpos[i]];
+            si = ps[order[rp]];
+            ii = pool[order[rp]];
         }
-        out_ids[rank] = ii;
-        out_sc[rank] = si;
+        int64_t rank = 0;
+        for (int64_t j0 = 0; j0 < ns; j0 += GRP_THREADS) {
+            __syncthreads();
+            if (j0 + t < ns) {
+                const int32_t rq = reppos[headpos[j0 + t]];
+                tsc[t] = ps[order[rq]];
+                tid_[t] = pool[order[rq]];
+            }
+            __syncthreads();
+            const int64_t lim = min((int64_t)GRP_THREADS, ns - j0);
+            if (i < ns)
+                for (int64_t j = 0; j < lim; j++)
+                    rank += (tsc[j] > si) || (tsc[j] == si && tid_[j] < ii);
+        }
+        if (i < ns) {
+            out_ids[rank] = ii;
+            out_sc[rank] = si;
+        }
     }
     for (int64_t i = ns + t; i < k; i += GRP_THREADS) {
         out_ids[i] = -1;
@@ -915,15 +1503,14 @@ __global__ __launch_bounds__(1024) void k_bitonic(const double* __restrict__ ps,
 
 // Values of the selected candidates: one wave per output row.
 __global__ __launch_bounds__(256) void k_values(const int64_t* __restrict__ ids, int64_t m,
-                                                SpaceDev sd, int streamed,
-                                                const int32_t* __restrict__ raw2c, Ops o, int n,
+                                                EvalCtx ev, Ops o, int n,
                                                 double* __restrict__ out, int64_t ldv) {
     const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (w >= m) return;
     const int lane = threadIdx.x & 63;
     const int64_t id = ids[w];
     Cand c;
-    const bool ok = id >= 0 && cand_of_id(sd, streamed, raw2c, id, c);
+    const bool ok = id >= 0 && cand_of_id(ev, id, c);
     for (int i = lane; i < n; i += 64)
         out[w * ldv + i] = ok ? cand_value(c, o, i) : __longlong_as_double(0x7FF8000000000000LL);
 }
@@ -973,6 +1560,26 @@ static void launch_pairs(int OPS, const PairArgs& a, bool list, int TP, hipStrea
     }
 }
 
+template <bool FP16>
+static void launch_lp(int cls, const PairArgs& a, const void* ylp, int ldl, hipStream_t st) {
+    const unsigned blocks = (unsigned)cdiv(a.n_tiles, 4);
+    if (!blocks) return;
+    switch (cls) {
+    case 31: k_screen_lp<31, FP16><<<blocks, 256, 0, st>>>(a, ylp, ldl); break;
+    case 28: k_screen_lp<28, FP16><<<blocks, 256, 0, st>>>(a, ylp, ldl); break;
+    default: DSC_FAIL(DISCOVER_E_UNSUPPORTED, "operator class %d", cls);
+    }
+}
+
+// Guard half-width of the precision forms (see k_screen_lp).
+static double lowprec_delta(int precision, int n) {
+    const double u = precision == DISCOVER_FP16_GUARD ? std::ldexp(1.0, -11) : std::ldexp(1.0, -8);
+    const double g = n * std::ldexp(1.0, -24);
+    double d = 2 * u + u * u + 1.01 * g / (1 - g) + 1e-12;
+    if (precision == DISCOVER_FP16_GUARD) d += std::ldexp(1.0, -24);
+    return d;
+}
+
 // Device-resident description of one search space and its work lists,
 // cached in the context: it depends only on (p, n, units, parameters).
 struct Plan {
@@ -989,10 +1596,18 @@ struct Plan {
     int64_t n_dtiles = 0;
     uint32_t dense_ops = 0;
     int dense_cls = 0;
+    int2* ptiles = nullptr;                   // (j, i0) tiles of one j for the precision form
+    int64_t n_ptiles = 0;
     int2* ltiles = nullptr;
     int32_t *ilist = nullptr, *icount = nullptr;
     int64_t n_ltiles = 0;
     uint32_t list_ops = 0;
+    int4* r3tiles = nullptr;                  // rung-3 tiles over rung-2 operands
+    int64_t n_r3tiles = 0;
+    int32_t* mat_unit = nullptr;
+    uint32_t r3_ops = 0;
+    std::vector<int2> h_ltiles;               // host copies used to derive rung-3 tiles
+    std::vector<int32_t> h_icount;
 
     template <class T>
     T* up(const std::vector<T>& v) {
@@ -1014,6 +1629,7 @@ static std::string plan_key(const discover_problem& pb, const discover_screen_pa
     k.append((const char*)&prm.rung, sizeof prm.rung);
     k.append((const char*)prm.rung_ops, sizeof prm.rung_ops);
     k.append((const char*)prm.rung_pool, sizeof prm.rung_pool);
+    k.append((const char*)&prm.precision, sizeof prm.precision);
     const int32_t dims[4] = {pb.p, pb.n, pb.B, pad_targets(pb.T)};
     k.append((const char*)dims, sizeof dims);
     if (pb.B && pb.units) k.append((const char*)pb.units, sizeof(int32_t) * pb.p * pb.B);
@@ -1077,6 +1693,13 @@ static std::shared_ptr<Plan> get_plan(discover_ctx* ctx, const discover_problem&
         }
         P->dtiles = P->up(tiles);
         P->n_dtiles = (int64_t)tiles.size();
+        std::vector<int2> pt;
+        for (int32_t j = jc0; j < jc1; j++) {
+            const int32_t ilim = std::min<int32_t>(i_end, j);
+            for (int32_t i0 = 0; i0 < ilim; i0 += 16 * LP_IB) pt.push_back(make_int2(j, i0));
+        }
+        P->ptiles = P->up(pt);
+        P->n_ptiles = (int64_t)pt.size();
     }
     if (P->list_ops) {
         std::vector<int2> tiles;
@@ -1106,6 +1729,37 @@ static std::shared_ptr<Plan> get_plan(discover_ctx* ctx, const discover_problem&
         P->ilist = P->up(il);
         P->icount = P->up(ic);
         P->n_ltiles = (int64_t)tiles.size();
+        if (sp.stream3) {            // keep the host copies for the rung-3 list tiles
+            P->h_ltiles = tiles;
+            P->h_icount = ic;
+        }
+    }
+    if (sp.stream3) {
+        // rung-3 candidates op3(i, j2): one wave per 64 rung-2 features j2
+        std::vector<int4> t3;
+        const int32_t c0 = sp.rung_start[1], c1 = sp.rung_start[2];
+        for (int o = 0; o < OP_ADD; o++) {
+            if (sd.block[2][o] < 0) continue;
+            for (int32_t l0 = c0; l0 < c1; l0 += 64) t3.push_back(make_int4(o, l0, 0, -2));
+        }
+        for (int o = OP_ADD; o <= OP_RDIV; o++) {
+            if (sd.block[2][o] < 0) continue;
+            const bool addcls = o <= OP_SUB;
+            if (units && addcls) {
+                for (size_t q = 0; q < P->h_ltiles.size(); q++)
+                    t3.push_back(make_int4(o, P->h_ltiles[q].x, P->h_ltiles[q].y, P->h_icount[q]));
+            } else {
+                for (int32_t l = c0; l < c1; l++)
+                    for (int32_t k0 = 0; k0 < l; k0 += 64) t3.push_back(make_int4(o, l, k0, -1));
+            }
+        }
+        P->r3tiles = P->up(t3);
+        P->n_r3tiles = (int64_t)t3.size();
+        std::vector<int32_t> mu(sp.mat_unit.begin(), sp.mat_unit.end());
+        if (mu.empty()) mu.push_back(0);
+        P->mat_unit = P->up(mu);
+        for (int o = OP_ADD; o <= OP_RDIV; o++)
+            if (sd.block[3][o] >= 0) P->r3_ops |= 1u << (o - OP_ADD);
     }
     ctx->plans[key] = P;
     return P;
@@ -1114,10 +1768,23 @@ static std::shared_ptr<Plan> get_plan(discover_ctx* ctx, const discover_problem&
 struct Problem {
     std::shared_ptr<Plan> plan;
     int n, T, Tl, TP, ldn, ldm, Mc;
-    double *Vf, *Rf, *Cf, *Vs, *Rs, *Cs, *mu, *mur, *Yc, *Yn, *syy, *ysum, *scores;
+    double *Vf, *Rf, *Cf, *Vs, *Rs, *Cs, *mu, *mur, *msq, *Yc, *Yn, *syy, *ysum, *scores;
     uint8_t* valid;
     int* bad;
     unsigned long long* nscored;
+    uint8_t* r2v = nullptr;                   // rung-2 operand statistics (streamed rung 3)
+    double* r2m = nullptr;
+    double* r2q = nullptr;
+    EvalCtx ev() const {
+        EvalCtx e;
+        e.sd = plan->sp.d;
+        e.streamed = plan->sp.streamed;
+        e.stream3 = plan->sp.stream3 ? 1 : 0;
+        e.raw2c = plan->raw2c;
+        e.valid = valid;
+        e.r2_valid = r2v;
+        return e;
+    }
 };
 
 // Materialise the operand features and screen every candidate into the
@@ -1144,6 +1811,7 @@ static void screen_problem(discover_ctx* ctx, const discover_problem& pb,
     P.Cf = ctx->buf<double>("Cf", (size_t)Mc * ldn);
     P.mu = ctx->buf<double>("mu", Mc);
     P.mur = ctx->buf<double>("mur", Mc);
+    P.msq = ctx->buf<double>("msq", Mc);
     P.valid = ctx->buf<uint8_t>("valid", Mc);
     P.Yc = ctx->buf<double>("Yc", (size_t)pb.T * ldn);
     P.Yn = ctx->buf<double>("Yn", (size_t)P.TP * ldn);
@@ -1168,18 +1836,26 @@ static void screen_problem(discover_ctx* ctx, const discover_problem& pb,
             k_mat_values<<<g, 256, 0, st>>>(n, ldn, c0, c1, pb.X, pb.ldx, pl.mat_op, pl.mat_a,
                                             pl.mat_b, pl.mat_raw, P.Vf);
             k_mat_stats<<<(unsigned)cdiv(c1 - c0, 4), 256, 0, st>>>(
-                n, ldn, c0, c1, pl.mat_a, pl.mat_b, P.Vf, P.Rf, P.Cf, P.mu, P.mur, P.valid);
+                n, ldn, c0, c1, pl.mat_op, pl.mat_a, pl.mat_b, P.Vf, P.Rf, P.Cf, P.mu, P.mur, P.msq,
+                P.valid);
         }
         check_launch("k_mat");
     }
     P.scores = ctx->buf<double>("scores", (size_t)P.Tl * N);
     DSC_HIP(hipMemsetAsync(P.scores, 0xFF, (size_t)P.Tl * N * 8, st));
     Ops ops{P.Vf, P.Rf, ldn};
+    const int64_t off2 = sp.stream3 ? sd.off[2] : 0, off3 = sp.stream3 ? sd.off[3] : 0;
+    if (sp.stream3) {
+        P.r2v = ctx->buf<uint8_t>("r2v", sd.L[2]);
+        P.r2m = ctx->buf<double>("r2m", sd.L[2]);
+        P.r2q = ctx->buf<double>("r2q", sd.L[2]);
+        DSC_HIP(hipMemsetAsync(P.r2v, 0, (size_t)sd.L[2], st));
+    }
     {
         KTimer kt(ctx, st, "screen_list");
         k_score_list<<<(unsigned)cdiv(pl.n_items, 4), 256, 0, st>>>(
             pl.items, pl.n_items, ops, P.valid, n, pb.T, prm.score_mode, P.Yc, P.syy, N, P.scores,
-            P.nscored);
+            P.nscored, P.r2v, P.r2m, P.r2q, off2, off3);
         check_launch("k_score_list");
     }
     const int R = sp.streamed;
@@ -1205,7 +1881,24 @@ static void screen_problem(discover_ctx* ctx, const discover_problem& pb,
     a.fix_cap = std::min<int64_t>(N, (int64_t)1 << 24);
     a.fix_ids = ctx->buf<int64_t>("fix_ids", a.fix_cap);
     a.fix_cnt = fix_cnt;
-    if (pl.dense_ops) {
+    a.r2v = P.r2v;
+    a.r2m = P.r2m;
+    a.r2q = P.r2q;
+    a.msq = P.msq;
+    if (pl.dense_ops && prm.precision != DISCOVER_FP64) {
+        const int ldl = (int)cdiv(n, 32) * 32;
+        void* ylp = ctx->raw("Ylp", (size_t)16 * ldl * 2);
+        dim3 gy((unsigned)cdiv(ldl, 256), 16);
+        const bool fp16 = prm.precision == DISCOVER_FP16_GUARD;
+        if (fp16) k_targets_lp<true><<<gy, 256, 0, st>>>(n, pb.T, ldn, ldl, P.Yn, (_Float16*)ylp);
+        else k_targets_lp<false><<<gy, 256, 0, st>>>(n, pb.T, ldn, ldl, P.Yn, (__bf16*)ylp);
+        a.tiles = pl.ptiles; a.ilist = nullptr; a.icount = nullptr;
+        a.n_tiles = pl.n_ptiles; a.opmask = pl.dense_ops;
+        KTimer kt(ctx, st, "screen_lp");
+        if (fp16) launch_lp<true>(pl.dense_cls, a, ylp, ldl, st);
+        else launch_lp<false>(pl.dense_cls, a, ylp, ldl, st);
+        check_launch("k_screen_lp");
+    } else if (pl.dense_ops) {
         a.tiles = pl.dtiles; a.ilist = nullptr; a.icount = nullptr;
         a.n_tiles = pl.n_dtiles; a.opmask = pl.dense_ops;
         KTimer kt(ctx, st, "screen_pairs");
@@ -1219,13 +1912,50 @@ static void screen_problem(discover_ctx* ctx, const discover_problem& pb,
         launch_pairs(3, a, true, P.TP, st);
         check_launch("k_screen_pairs(list)");
     }
+    const EvalCtx ev = P.ev();
     {
         // exact decision for the ill-conditioned ones (persistent waves over
         // the device-side count)
         KTimer kt(ctx, st, "screen_fixup");
         k_fixup<DISCOVER_MAX_TARGETS><<<1024, 256, 0, st>>>(
-            a.fix_ids, a.fix_cnt, a.fix_cap, sd, sp.streamed, pl.raw2c, P.valid, ops, n, pb.T,
-            prm.score_mode, P.Yc, P.syy, N, P.scores, P.nscored);
+            a.fix_ids, a.fix_cnt, a.fix_cap, ev, ops, n, pb.T, prm.score_mode, P.Yc, P.syy, N,
+            P.scores, P.nscored, P.r2v, P.r2m, P.r2q);
+        check_launch("k_fixup");
+    }
+    if (!sp.stream3 || !pl.r3_ops || !pl.n_r3tiles) return;
+    // operator-limited rung 3 on top of the rung-2 operand statistics
+    unsigned long long* fix3 = ctr + 3;
+    R3Args g3{};
+    g3.tiles = pl.r3tiles; g3.klist = pl.ilist; g3.n_tiles = pl.n_r3tiles;
+    g3.n = n; g3.ldm = ldm; g3.ldn = ldn; g3.Mc = Mc;
+    g3.c1_lo = sp.rung_start[1]; g3.c1_hi = sp.rung_start[2];
+    g3.pe = sp.rung_start[sd.pool[3] + 1];
+    g3.B = sp.B;
+    g3.Vs = P.Vs; g3.Rs = P.Rs; g3.Cs = P.Cs; g3.Vf = P.Vf; g3.Rf = P.Rf; g3.Cf = P.Cf;
+    g3.mu = P.mu; g3.mur = P.mur; g3.valid = P.valid; g3.mat_raw = pl.mat_raw;
+    g3.mat_unit = pl.mat_unit; g3.r2v = P.r2v; g3.r2m = P.r2m; g3.r2q = P.r2q; g3.msq = P.msq;
+    g3.Yn = P.Yn; g3.ysum = P.ysum; g3.T = pb.T; g3.mode = prm.score_mode;
+    g3.opmask = pl.r3_ops; g3.sd = sd; g3.N = N; g3.scores = P.scores; g3.nscored = P.nscored;
+    g3.fix_cap = a.fix_cap;
+    g3.fix_ids = ctx->buf<int64_t>("fix_ids3", g3.fix_cap);
+    g3.fix_cnt = fix3;
+    {
+        KTimer kt(ctx, st, "screen_r3");
+        const unsigned blocks = (unsigned)cdiv(g3.n_tiles, 4);
+        switch (P.TP) {
+        case 1: k_screen_r3<31, 2, 1><<<blocks, 256, 0, st>>>(g3); break;
+        case 2: k_screen_r3<31, 2, 2><<<blocks, 256, 0, st>>>(g3); break;
+        case 4: k_screen_r3<31, 1, 4><<<blocks, 256, 0, st>>>(g3); break;
+        case 8: k_screen_r3<31, 1, 8><<<blocks, 256, 0, st>>>(g3); break;
+        default: k_screen_r3<31, 1, 16><<<blocks, 256, 0, st>>>(g3); break;
+        }
+        check_launch("k_screen_r3");
+    }
+    {
+        KTimer kt(ctx, st, "screen_fixup");
+        k_fixup<DISCOVER_MAX_TARGETS><<<1024, 256, 0, st>>>(
+            g3.fix_ids, g3.fix_cnt, g3.fix_cap, ev, ops, n, pb.T, prm.score_mode, P.Yc, P.syy, N,
+            P.scores, P.nscored, nullptr, nullptr, nullptr);
         check_launch("k_fixup");
     }
 }
@@ -1250,6 +1980,8 @@ static void select_list(discover_ctx* ctx, const discover_problem& pb,
     int64_t* stv = ctx->buf<int64_t>("selst", 2);
     unsigned long long* cnt = ctx->buf<unsigned long long>("poolcnt", 1);
     int64_t* res = ctx->buf<int64_t>("groupres", 8);
+    unsigned long long* maxerr = ctx->buf<unsigned long long>("maxerr", 1);
+    DSC_HIP(hipMemsetAsync(maxerr, 0, 8, st));
     Ops ops{P.Vf, P.Rf, P.ldn};
     int64_t cap = 4 * K + 4096;
     int64_t fcap = 64 * cap;
@@ -1278,8 +2010,8 @@ static void select_list(discover_ctx* ctx, const discover_problem& pb,
         {
             KTimer kt(ctx, st, "rescore");
             k_rescore<DISCOVER_MAX_TARGETS><<<(unsigned)std::min<int64_t>(2048, cdiv(cap, 4)), 256, 0, st>>>(
-                pool, cnt, cap, sp.d, sp.streamed, pl.raw2c, P.valid, ops, P.n, P.T, prm.score_mode, t,
-                P.Yc, P.syy, pb.exclude, pb.exclude ? pb.n_exclude : 0, ps, pex);
+                pool, cnt, cap, P.ev(), ops, P.n, P.T, prm.score_mode, t,
+                P.Yc, P.syy, pb.exclude, pb.exclude ? pb.n_exclude : 0, ps, pex, sc, maxerr);
             check_launch("k_rescore");
         }
         {
@@ -1292,8 +2024,7 @@ static void select_list(discover_ctx* ctx, const discover_problem& pb,
         }
         if (prm.dedup) {
             KTimer kt(ctx, st, "dedup_pairs");
-            k_pairs<<<2048, 256, 0, st>>>(pool, order, lo, off, cnt, cap, sp.d, sp.streamed, pl.raw2c,
-                                          ops, P.n, flag, fcap);
+            k_pairs<<<2048, 256, 0, st>>>(pool, order, lo, off, cnt, cap, P.ev(), ops, P.n, flag, fcap);
             check_launch("k_pairs");
         }
         {
@@ -1305,7 +2036,9 @@ static void select_list(discover_ctx* ctx, const discover_problem& pb,
         }
         int64_t h_res[8];
         int h_bad = 0;
+        double h_err = 0.0;
         DSC_HIP(hipMemcpyAsync(h_res, res, sizeof h_res, hipMemcpyDeviceToHost, st));
+        DSC_HIP(hipMemcpyAsync(&h_err, maxerr, 8, hipMemcpyDeviceToHost, st));
         DSC_HIP(hipMemcpyAsync(&h_bad, P.bad, sizeof h_bad, hipMemcpyDeviceToHost, st));
         DSC_HIP(hipStreamSynchronize(st));
         if (h_bad) DSC_FAIL(DISCOVER_E_NUMERIC, "a target column is constant or not finite");
@@ -1321,6 +2054,7 @@ static void select_list(discover_ctx* ctx, const discover_problem& pb,
             continue;
         }
         stats.pool_size += h_res[4];
+        stats.max_lowprec_err = std::max(stats.max_lowprec_err, h_err);
         if (h_res[1] || K >= N) {
             stats.n_selected += h_res[0];
             stats.n_merged += h_res[2];
@@ -1377,8 +2111,6 @@ extern "C" discover_status discover_generate_screen(discover_ctx* ctx, const dis
         validate(probs, n_problems, prm, out_ids, out_scores, out_values, ldv);
         DSC_HIP(hipSetDevice(ctx->device));
         hipStream_t st = (hipStream_t)stream;
-        if (prm->precision != DISCOVER_FP64)
-            DSC_FAIL(DISCOVER_E_UNSUPPORTED, "reduced-precision screening is not built in this library");
         int64_t row = 0;
         for (int b = 0; b < n_problems; b++) {
             const discover_problem& pb = probs[b];
@@ -1387,7 +2119,11 @@ extern "C" discover_status discover_generate_screen(discover_ctx* ctx, const dis
             screen_problem(ctx, pb, *prm, P, st);
             stats.n_raw = P.plan->sp.n_raw();
             stats.n_unit_valid = P.plan->sp.n_unit_valid;
-            const double margin = 4.0 * P.n * EPS64 * KAPPA_MAX;
+            double margin = 4.0 * P.n * EPS64 * KAPPA_MAX;
+            if (prm->precision != DISCOVER_FP64) {
+                stats.guard_band = lowprec_delta(prm->precision, P.n);
+                margin = std::max(margin, stats.guard_band);
+            }
             const int Tl = P.Tl;
             for (int t = 0; t < Tl; t++) {
                 select_list(ctx, pb, *prm, P, t, margin, out_ids + (row + t) * prm->k,
@@ -1397,8 +2133,7 @@ extern "C" discover_status discover_generate_screen(discover_ctx* ctx, const dis
                 KTimer kt(ctx, st, "values");
                 Ops ops{P.Vf, P.Rf, P.ldn};
                 const int64_t m = (int64_t)Tl * prm->k;
-                k_values<<<(unsigned)cdiv(m, 4), 256, 0, st>>>(out_ids + row * prm->k, m, P.plan->sp.d,
-                                                               P.plan->sp.streamed, P.plan->raw2c, ops, P.n,
+                k_values<<<(unsigned)cdiv(m, 4), 256, 0, st>>>(out_ids + row * prm->k, m, P.ev(), ops, P.n,
                                                                out_values + row * prm->k * ldv, ldv);
                 check_launch("k_values");
             }

@@ -94,8 +94,20 @@ void build_space(Space& sp, int p, const discover_screen_params& prm, int B,
     for (int r = d.R + 1; r < 4; r++)
         for (int o = 0; o < 10; o++) d.block[r][o] = -1;
 
-    sp.streamed = d.R >= 1 ? d.R : 0;
-    sp.M_raw = d.R >= 1 ? d.off[d.R] : p;
+    // Rung 3 is supported as an operator-limited rung: binary operators whose
+    // first operand comes from a materialised rung (partner pool <= 1); the
+    // rung-2 operand is regenerated on the fly from two rung-1 features.
+    sp.stream3 = d.R == 3;
+    if (sp.stream3) {
+        if (d.pool[3] > 1)
+            DSC_FAIL(DISCOVER_E_UNSUPPORTED,
+                     "rung 3 needs an operator-limited partner pool (rung_pool[3] <= 1)");
+        for (int o = 0; o < OP_ADD; o++)
+            if (d.block[3][o] >= 0)
+                DSC_FAIL(DISCOVER_E_UNSUPPORTED, "unary operators at rung 3 are not supported");
+    }
+    sp.streamed = d.R >= 1 ? (sp.stream3 ? 2 : d.R) : 0;
+    sp.M_raw = sp.streamed ? d.off[sp.streamed] : p;
     DSC_REQUIRE(sp.M_raw <= (int64_t)1 << 22,
                 "operand features below the streamed rung (%lld) exceed the HBM plan",
                 (long long)sp.M_raw);
@@ -201,6 +213,43 @@ void build_space(Space& sp, int p, const discover_screen_params& prm, int B,
             }
         }
         sp.n_unit_valid_streamed = cnt;
+        sp.n_unit_valid += cnt;
+    }
+    if (sp.stream3) {
+        // unit-valid rung-3 candidates: for every unit-legal rung-2 feature,
+        // the legal partners in the pool (any for mul/div/rdiv, same
+        // exponents for add/sub)
+        const int32_t pe = sp.rung_start[d.pool[3] + 1];
+        std::unordered_map<std::string, int64_t> pu;
+        auto ukey = [&](const int32_t* u) {
+            return std::string((const char*)u, sizeof(int32_t) * Bq);
+        };
+        for (int32_t c = 0; c < pe; c++) pu[ukey(&sp.mat_unit[(size_t)c * Bq])]++;
+        const int nmul = (d.block[3][OP_MUL] >= 0) + (d.block[3][OP_DIV] >= 0) + (d.block[3][OP_RDIV] >= 0);
+        const int nadd = (d.block[3][OP_ADD] >= 0) + (d.block[3][OP_SUB] >= 0);
+        const int32_t c0 = sp.rung_start[1], c1 = sp.rung_start[2];
+        std::vector<int32_t> u2(Bq);
+        int64_t cnt = 0;
+        auto count_j2 = [&](const int32_t* u) {
+            cnt += (int64_t)nmul * pe;
+            if (nadd) {
+                auto it = pu.find(ukey(u));
+                if (it != pu.end()) cnt += (int64_t)nadd * it->second;
+            }
+        };
+        for (int o = 0; o < OP_ADD; o++) {
+            if (d.block[2][o] < 0) continue;
+            for (int32_t c = c0; c < c1; c++)
+                if (unit_rule(o, B, &sp.mat_unit[(size_t)c * Bq], nullptr, u2.data())) count_j2(u2.data());
+        }
+        for (int o = OP_ADD; o <= OP_RDIV; o++) {
+            if (d.block[2][o] < 0) continue;
+            for (int32_t l = c0; l < c1; l++)
+                for (int32_t k = 0; k < l; k++)
+                    if (unit_rule(o, B, &sp.mat_unit[(size_t)k * Bq], &sp.mat_unit[(size_t)l * Bq], u2.data()))
+                        count_j2(u2.data());
+        }
+        sp.n_unit_valid_r3 = cnt;
         sp.n_unit_valid += cnt;
     }
 }

@@ -81,6 +81,8 @@ struct Space {
     SpaceDev d{};
     int B = 0;
     int streamed = 0;                  // rung whose candidates are streamed (0: none)
+    bool stream3 = false;              // rung 3 (operator-limited) streamed on top of rung 2
+    int64_t n_unit_valid_r3 = 0;       // unit-valid candidates of rung 3
     int64_t M_raw = 0;                 // raw features below the streamed rung
     std::vector<int64_t> mat_raw;      // compact -> raw index (ascending)
     std::vector<int32_t> raw2c;        // raw -> compact or -1 (size M_raw)

@@ -276,3 +276,75 @@ def test_omp_against_oracle(torch, ctx, D, oracle_mod, init):
     assert act.cpu().numpy().tolist() == act_o
     np.testing.assert_allclose(coef.cpu().numpy(), coef_o, rtol=1e-10, atol=1e-10 * np.max(np.abs(coef_o)))
     assert abs(float(rmse[0]) - rmse_o) <= 1e-10 * rmse_o
+
+
+# ------------------------------------------------------------ precision forms
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_precision_multitarget(torch, ctx, D, oracle_mod, prec):
+    """16 targets at once through the MFMA form: every per-target top-20
+    equals the FP64 oracle's, and the measured low-precision error stays
+    inside the guard half-width."""
+    import synth
+    O = oracle_mod
+    w = synth.multitarget16()
+    sp = O.Space.of(w)
+    lists, status, nvalid = O.sis(sp, w["X"], None, w["Y"], w["k"], (), "per_target")
+    q = prm_of(D, w, mode="per_target")
+    q.precision = D.BF16_GUARD if prec == "bf16" else D.FP16_GUARD
+    ids, sc, _, st = ctx.generate_screen(dev(torch, w["X"]), dev(torch, w["Y"]), q)
+    for t in range(16):
+        check_selection(ids[t].cpu().numpy(), sc[t].cpu().numpy(), lists[t][0], lists[t][1],
+                        what="%s target %d" % (prec, t))
+    assert 0 < st["guard_band"] < 0.01
+    assert st["max_lowprec_err"] <= st["guard_band"]
+
+
+@pytest.mark.parametrize("prec,T,B,rung", [("bf16", 8, 0, 2), ("fp16", 8, 0, 2), ("bf16", 16, 2, 2),
+                                           ("fp16", 3, 3, 2), ("bf16", 1, 0, 2)])
+def test_precision_max_mode(torch, ctx, D, oracle_mod, prec, T, B, rung):
+    """Several residual-like targets scored by their maximum |r| (one list)."""
+    O = oracle_mod
+    rng = np.random.default_rng(T * 7 + B)
+    p, n = 6, 203
+    X = rng.lognormal(0, 0.4, size=(p, n))
+    units = rng.integers(-1, 2, size=(p, B)).astype(np.int32) if B else None
+    if B:
+        units[:2] = 0
+    Y = np.array([X[t % p] * X[(t + 1) % p] + rng.normal(size=n) * (0.2 + 0.1 * t) for t in range(T)])
+    sp = O.Space(p, rung, O.OPS)
+    (lst,), status, nvalid = O.sis(sp, X, units, Y, 60, (), "max")
+    q = D.params(rung=rung, k=60, score_mode=D.SCORE_MAX,
+                 precision=D.BF16_GUARD if prec == "bf16" else D.FP16_GUARD)
+    ids, sc, _, st = ctx.generate_screen(dev(torch, X), dev(torch, Y), q, units=units)
+    check_selection(ids[0].cpu().numpy(), sc[0].cpu().numpy(), lst[0], lst[1], what="max %s" % prec)
+    assert st["n_scored"] == nvalid
+    assert st["max_lowprec_err"] <= st["guard_band"]
+
+
+# ------------------------------------------------------- operator-limited rung 3
+@pytest.mark.parametrize("seed,p,n,B,T,mode", [(0, 4, 61, 0, 1, "per_target"), (1, 5, 130, 2, 1, "per_target"),
+                                               (2, 4, 97, 0, 3, "max"), (3, 5, 64, 3, 2, "max")])
+def test_screen_rung3_limited(torch, ctx, D, oracle_mod, seed, p, n, B, T, mode):
+    """Rung 3 restricted to binary operators with a primary partner: the
+    rung-2 operand of every rung-3 candidate is regenerated on the fly."""
+    O = oracle_mod
+    rng = np.random.default_rng(300 + seed)
+    X = rng.lognormal(0, 0.4, size=(p, n))
+    units = rng.integers(-1, 2, size=(p, B)).astype(np.int32) if B else None
+    if B:
+        units[:2] = 0
+    Y = np.array([X[0] * X[1] * X[-1] + 0.2 * X[2] + 0.05 * (t + 1) * rng.normal(size=n) for t in range(T)])
+    rung_ops = [None, None, None, ("add", "sub", "mul", "div", "rdiv")]
+    rung_pool = [None, None, None, 0]
+    sp = O.Space(p, 3, O.OPS, rung_ops, rung_pool)
+    lists, status, nvalid = O.sis(sp, X, units, Y, 30, (), mode)
+    q = D.params(rung=3, k=30, rung_ops=rung_ops, rung_pool=rung_pool,
+                 score_mode=D.SCORE_MAX if mode == "max" else D.SCORE_PER_TARGET)
+    ids, sc, vals, st = ctx.generate_screen(dev(torch, X), dev(torch, Y), q, units=units)
+    for t, (li, ls, _) in enumerate(lists):
+        check_selection(ids[t].cpu().numpy(), sc[t].cpu().numpy(), li, ls, what="r3 list %d" % t)
+    assert st["n_raw"] == sp.N
+    assert st["n_unit_valid"] == int((status != O.ST_UNIT).sum())
+    assert st["n_scored"] == nvalid
+    V, _ = O.values(sp, X, units, ids[0].cpu().numpy())
+    np.testing.assert_allclose(vals[0].cpu().numpy(), V, rtol=1e-12, atol=0)

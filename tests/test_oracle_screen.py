@@ -90,7 +90,11 @@ def test_scores_against_brute_force(oracle_mod, p, R, seed):
     for lv in brute.trees_by_depth(p, R, O.OPS):
         for t in lv:
             v = brute.evaluate(t, X)
-            if np.all(np.isfinite(v)) and np.std(v) > 1e-8 * np.sqrt(np.mean(v * v)):
+            ok = np.all(np.isfinite(v)) and np.std(v) > 1e-8 * np.sqrt(np.mean(v * v))
+            if ok and t[0] in ("add", "sub"):
+                va, vb = brute.evaluate(t[1], X), brute.evaluate(t[2], X)
+                ok = np.sum(v * v) > 1e-20 * np.sum(va * va + vb * vb)
+            if ok:
                 ref[brute.canon(t)] = abs(np.corrcoef(v, y)[0, 1])
     for cid in range(sp.N):
         key = brute.canon(brute.oracle_tree(sp, cid))
@@ -209,3 +213,23 @@ def test_max_mode_scores(oracle_mod):
     m = O.combine_scores(r, "max")
     assert m.shape == (1, 100) and np.isnan(m[0, 5])
     assert np.allclose(np.delete(m[0], 5), np.delete(np.abs(r).max(axis=0), 5))
+
+
+def test_cancellation_rule(oracle_mod):
+    """A sum or difference that cancels to rounding noise (x - exp(log x),
+    x - sqrt(sq x)) is constant whatever the math library's last bits; a
+    genuinely small difference (relative size 1e-6) is not."""
+    O = oracle_mod
+    rng = np.random.default_rng(9)
+    n = 50
+    X = rng.uniform(0.5, 2.0, size=(3, n))
+    X[1] = X[0] * (1 + 1e-6 * rng.normal(size=n))
+    sp = O.Space(3, 3, O.OPS, [None, None, None, ("sub",)], [None, None, None, 0])
+    names = {"(x0 - exp(log(x0)))", "(x0 - sqrt(sq(x0)))", "(x2 - inv(inv(x2)))"}
+    ids = [i for i in range(sp.levels[:3].sum(), sp.N) if sp.expr(i) in names]
+    assert len(ids) == 3
+    _, st = O.values(sp, X, None, ids)
+    assert all(v == O.ST_CONST for v in st)
+    small = [i for i in range(sp.levels[0], sp.levels[:2].sum()) if sp.expr(i) == "(x0 - x1)"]
+    _, st = O.values(sp, X, None, small)
+    assert st[0] == O.ST_VALID
