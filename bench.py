@@ -33,43 +33,24 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-oracle", action="store_true", help="skip the parity gate and CPU baseline")
-    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     return ap.parse_args()
 
 
-def cpu_baseline(w, budget_s):
-    """The oracle as it stands, timed on this host on a bounded sample of
-    the same workload: one full screening pass (every candidate of the
-    space against y) plus exhaustive Gram-mode L0 (D = 3) over the first S'
-    rows of a subspace, S' chosen to fit the time budget."""
-    import numpy as np
+def oracle_step(w, omp_D):
+    """The oracle as it stands, run over one whole step of the same workload
+    on this host's cores (screening of every candidate for d = 1..3,
+    exhaustive L0 over the union subspace, OMP); returns its result, the
+    wall time and the items it processed, counted from its own output."""
     from oracle import oracle as O
-    sp = O.Space.of(w)
     t0 = time.perf_counter()
-    (sel,), status, nvalid = O.sis(sp, w["X"], w["units"], w["Y"][:1], w["k"])
-    t_screen = time.perf_counter() - t0
-    n_unit_valid = int((status != O.ST_UNIT).sum())
-    V, _ = O.values(sp, w["X"], w["units"], sel[0])
-    rng = np.random.default_rng(0)
-    F = np.vstack([V, V * rng.uniform(0.9, 1.1, size=V.shape)])   # 1000 rows to sample from
-    S = 120
-    t_l0 = 0.0
-    subsets = 0
-    while True:
-        t1 = time.perf_counter()
-        O.l0(F[:S], np.arange(S), w["Y"][0], 3, mode="gram")
-        dt = time.perf_counter() - t1
-        if t_screen + dt > budget_s or S >= 1000:
-            t_l0, subsets = dt, math.comb(S, 3)
-            break
-        t_l0, subsets = dt, math.comb(S, 3)
-        S = min(1000, int(S * 1.35))
-    items = n_unit_valid + subsets
-    return {"value": items / (t_screen + t_l0), "unit": "items/s",
-            "cores": int(O.lib().or_max_threads()), "kind": "oracle",
-            "sample": "one oracle screening pass over all %d candidates (%d unit-valid) in %.2f s "
-                      "+ Gram-mode L0 D=3 over %d rows (%d subsets) in %.2f s"
-                      % (sp.N, n_unit_valid, t_screen, S, subsets, t_l0)}
+    ref = O.sisso(dict(w, omp_D=omp_D))
+    dt = time.perf_counter() - t0
+    screened = sum(int((d["status"] != O.ST_UNIT).sum()) for d in ref["dims"])
+    subsets, S = 0, 0
+    for d, dd in enumerate(ref["dims"], 1):
+        S += len(dd["sel_ids"])
+        subsets += math.comb(S, d)
+    return ref, dt, screened + subsets, int(O.lib().or_max_threads())
 
 
 def main():
@@ -144,22 +125,29 @@ def main():
                    "candidates_screened_per_step": screened, "subsets_fitted_per_step": subsets},
         "screen_rate": screened / (screen_ms * 1e-3) if screen_ms else None,
         "l0_rate": subsets / (l0_ms * 1e-3) if l0_ms else None,
+        "pair_tile_j": out["dims"][0]["screen_stats"]["tile_j"],
         "kernels": kern,
         "roofline": roofline,
     }
     if not args.no_oracle:
-        from oracle import oracle as O
-        ref = O.sisso(w)
+        ref, t_cpu, items_cpu, cores = oracle_step(w, omp_D)
         S_g = out["S_ids"].cpu().numpy()
         ok = True
         for rd, gd in zip(ref["dims"], out["dims"]):
             win_g = sorted(int(S_g[i]) for i in gd["subsets"][0].cpu().numpy())
             ok &= win_g == sorted(rd["models"][0]["ids"])
             ok &= set(gd["sel_ids"].cpu().numpy().tolist()) == set(rd["sel_ids"].tolist())
+        omp_g = [int(S_g[i]) for i in out["omp"]["active"].cpu().numpy()]
+        ok &= sorted(omp_g) == sorted(ref["omp"]["ids"])
+        ok &= items_cpu == screened + subsets
         line["parity"] = "pass" if ok else "FAIL"
         if not ok:
             line["value"] = None
-        line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+        line["cpu_baseline"] = {
+            "value": items_cpu / t_cpu, "unit": "items/s", "cores": cores, "kind": "oracle",
+            "sample": "one whole step of the same workload by the FP64 oracle (%d unit-valid "
+                      "candidates screened over d = 1..3, %d L0 subsets, OMP to %d): %.2f s"
+                      % (screened, subsets, omp_D, t_cpu)}
     print(json.dumps(line))
 
 

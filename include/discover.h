@@ -122,6 +122,10 @@ typedef struct {
     int32_t score_mode;       /* DISCOVER_SCORE_PER_TARGET or DISCOVER_SCORE_MAX */
     int32_t precision;        /* DISCOVER_FP64, DISCOVER_BF16_GUARD or DISCOVER_FP16_GUARD */
     int32_t dedup;            /* 1: duplicate groups are merged (default); 0: off */
+    int32_t tile_j;           /* FP64 dense pair kernel tile width: 0 = autotuned
+                                 (default), or 1, 2, 4 operand features per wave
+                                 (capped by what the target count allows); the
+                                 scores do not depend on it */
 } discover_screen_params;
 
 /* Per-problem counters of one screening call (host memory). */
@@ -135,6 +139,10 @@ typedef struct {
     int64_t n_selected;       /* selected features (summed over lists) */
     double  max_lowprec_err;  /* precision forms: max |s_lowprec - s_fp64| over the pool */
     double  guard_band;       /* precision forms: the guard half-width used */
+    int32_t tile_j;           /* FP64 dense pair kernel: operand features per wave,
+                                 chosen by timing 1/2/4 on the first call for a
+                                 search space (0 when that kernel did not run) */
+    int32_t reserved;
 } discover_screen_stats;
 
 /* Enumerate the candidates of P_R (rungs 0..R), drop those failing the unit

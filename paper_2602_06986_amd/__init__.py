@@ -38,14 +38,14 @@ class Problem(C.Structure):
 class ScreenParams(C.Structure):
     _fields_ = [("ops", C.c_uint32), ("rung", C.c_int32), ("rung_ops", C.c_uint32 * 4),
                 ("rung_pool", C.c_int32 * 4), ("k", C.c_int32), ("score_mode", C.c_int32),
-                ("precision", C.c_int32), ("dedup", C.c_int32)]
+                ("precision", C.c_int32), ("dedup", C.c_int32), ("tile_j", C.c_int32)]
 
 
 class ScreenStats(C.Structure):
     _fields_ = [("n_raw", C.c_int64), ("n_unit_valid", C.c_int64), ("n_scored", C.c_int64),
                 ("pool_size", C.c_int64), ("pool_rounds", C.c_int64), ("n_merged", C.c_int64),
                 ("n_selected", C.c_int64), ("max_lowprec_err", C.c_double),
-                ("guard_band", C.c_double)]
+                ("guard_band", C.c_double), ("tile_j", C.c_int32), ("reserved", C.c_int32)]
 
     def asdict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -107,7 +107,7 @@ def _check(code):
 
 
 def params(ops=OPS, rung=1, k=20, score_mode=SCORE_PER_TARGET, precision=FP64, dedup=True,
-           rung_ops=None, rung_pool=None):
+           rung_ops=None, rung_pool=None, tile_j=0):
     """Build the screening parameter struct from operator names."""
     prm = ScreenParams()
     prm.ops = sum(OP_BIT[o] for o in ops)
@@ -121,6 +121,7 @@ def params(ops=OPS, rung=1, k=20, score_mode=SCORE_PER_TARGET, precision=FP64, d
     prm.score_mode = score_mode
     prm.precision = precision
     prm.dedup = 1 if dedup else 0
+    prm.tile_j = tile_j
     return prm
 
 

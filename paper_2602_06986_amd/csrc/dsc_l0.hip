@@ -103,7 +103,8 @@ __global__ __launch_bounds__(256) void k_gram(int M, int ldz, int nk, const doub
 struct SweepArgs {
     const double* G;
     int ldg, S, D;
-    const int2* items;        // D = 1, 2: (a, first b) per wave; D = 3: (a, first c) per block
+    const int2* items;        // D = 1, 2: (a, first b) per wave
+    const int4* items3;       // D = 3: (a0, c0, b_lo, b_hi) per block
     int64_t n_items;
     double* lane_q;           // [n_items][64] (D = 1, 2) or [n_items][256] (D = 3)
 };
@@ -193,8 +194,8 @@ __device__ __forceinline__ double sw3_q(const double4& e, const Sw3Lane& L, doub
 
 __global__ __launch_bounds__(256) void k_sweep3(SweepArgs g) {
     __shared__ double4 tab[4 * SW3_A][SW3_CHUNK];
-    const int2 item = g.items[blockIdx.x];
-    const int a0 = item.x, c0 = item.y;                  // block: a0..a0+15, c0..c0+63
+    const int4 item = g.items3[blockIdx.x];
+    const int a0 = item.x, c0 = item.y;                  // block: a0..a0+15, c0..c0+63, b in [z, w)
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int c = c0 + lane;
     double* out = g.lane_q + ((int64_t)blockIdx.x * 4 + wv) * (SW3_A * 64);
@@ -225,8 +226,8 @@ __global__ __launch_bounds__(256) void k_sweep3(SweepArgs g) {
         best[k] = -1.0;
     }
     const double* colc = g.G + cc;
-    const int bend = min(g.S - 1, c0 + 63);              // b < largest c of the block
-    for (int b0 = a0 + 1; b0 < bend; b0 += SW3_CHUNK) {
+    const int bend = min(min(g.S - 1, c0 + 63), item.w); // b < largest c of the block
+    for (int b0 = max(a0 + 1, item.z); b0 < bend; b0 += SW3_CHUNK) {
         const int nb = min(SW3_CHUNK, bend - b0);
         __syncthreads();
         // stage (a, b) factors for the block's 16 values of a
@@ -278,7 +279,8 @@ struct BandArgs {
     int4* band;
     unsigned long long* bcnt;
     int64_t bcap;
-    int2* pairs;              // D = 3: (a, c) lanes to expand
+    const int4* items3;
+    int4* pairs;              // D = 3: (a, c, b_lo, b_hi) lanes to expand
     unsigned long long* pcnt;
     int64_t pcap;
 };
@@ -300,15 +302,15 @@ __global__ __launch_bounds__(256) void k_band_lanes(BandArgs g) {
          i += (int64_t)gridDim.x * 256) {
         const double q = g.lane_q[i];
         if (!(q > -0.5) || q < thr - 1e-9) continue;
-        const int2 it = g.items[i / per];
         const int lane = (int)(i % per);
-        if (g.D == 1) band_push(g, it.y + lane, -1, -1);
-        else if (g.D == 2) band_push(g, it.x, it.y + lane, -1);
+        if (g.D == 1) band_push(g, g.items[i / per].y + lane, -1, -1);
+        else if (g.D == 2) band_push(g, g.items[i / per].x, g.items[i / per].y + lane, -1);
         else {
             // lane index within a D = 3 block: ((wave * SW3_A) + k) * 64 + c lane
+            const int4 it = g.items3[i / per];
             const int wk = lane / 64, cl = lane % 64;
             const unsigned long long slot = atomicAdd(g.pcnt, 1ull);
-            if ((int64_t)slot < g.pcap) g.pairs[slot] = make_int2(it.x + wk, it.y + cl);
+            if ((int64_t)slot < g.pcap) g.pairs[slot] = make_int4(it.x + wk, it.y + cl, it.z, it.w);
         }
     }
 }
@@ -320,6 +322,7 @@ __global__ __launch_bounds__(256) void k_band_expand3(BandArgs g) {
     const int lane = threadIdx.x & 63;
     for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < np; i += (int64_t)gridDim.x * 4) {
         const int a = g.pairs[i].x, c = g.pairs[i].y;
+        const int blo = max(a + 1, g.pairs[i].z), bhi = min(c, g.pairs[i].w);
         const double* Ga = g.G + (int64_t)a * g.ldg;
         const double caa = Ga[a], ca = Ga[g.S];
         const double ica = 1.0 / caa;
@@ -328,7 +331,7 @@ __global__ __launch_bounds__(256) void k_band_expand3(BandArgs g) {
         L.upc = uc * ica;
         L.dc = g.G[(int64_t)c * g.ldg + c] - uc * L.upc;
         L.zc = g.G[(int64_t)c * g.ldg + g.S] - ca * L.upc;
-        for (int b = a + 1 + lane; b < c; b += 64) {
+        for (int b = blo + lane; b < bhi; b += 64) {
             const double4 e = sw3_b_entry(g.G, g.ldg, g.S, Ga, ica, ca, b);
             if (e.w < 0.0) continue;
             double den;
@@ -630,22 +633,28 @@ static void prep_gram(discover_ctx* ctx, const discover_l0_problem& pb, L0Plan& 
 // are dealt to the 8 XCDs by longest-processing-time on their total work,
 // and block p of the grid runs on XCD p mod 8, so each XCD's L2 holds only
 // its own columns of G; within an XCD the heaviest blocks go first.
-static std::vector<int2> sweep3_blocks(int S) {
+constexpr int SW3_BMAX = 256;         // b iterations per block (bounds the critical path)
+
+static std::vector<int4> sweep3_blocks(int S) {
     const int ngrp = (S + 63) / 64;
-    std::vector<std::vector<std::pair<int64_t, int2>>> per_grp(ngrp);
+    std::vector<std::vector<std::pair<int64_t, int4>>> per_grp(ngrp);
     std::vector<int64_t> gwork(ngrp, 0);
     for (int g = 0; g < ngrp; g++) {
         const int c0 = 64 * g, ch = std::min(S, c0 + 64);
         for (int a0 = 0; a0 < S - 2 && a0 + 2 < ch; a0 += 16) {
-            const int64_t work = (int64_t)(ch - 1 - a0) * 16;
-            per_grp[g].push_back({work, make_int2(a0, c0)});
-            gwork[g] += work;
+            const int bend = std::min(S - 1, c0 + 63);
+            for (int b0 = a0 + 1; b0 < bend; b0 += SW3_BMAX) {
+                const int b1 = std::min(bend, b0 + SW3_BMAX);
+                const int64_t work = (int64_t)(b1 - b0) * 16;
+                per_grp[g].push_back({work, make_int4(a0, c0, b0, b1)});
+                gwork[g] += work;
+            }
         }
     }
     std::vector<int> order(ngrp);
     for (int g = 0; g < ngrp; g++) order[g] = g;
     std::sort(order.begin(), order.end(), [&](int x, int y) { return gwork[x] > gwork[y]; });
-    std::vector<std::vector<std::pair<int64_t, int2>>> q(8);
+    std::vector<std::vector<std::pair<int64_t, int4>>> q(8);
     std::vector<int64_t> xwork(8, 0);
     for (int g : order) {
         const int x = (int)(std::min_element(xwork.begin(), xwork.end()) - xwork.begin());
@@ -654,16 +663,16 @@ static std::vector<int2> sweep3_blocks(int S) {
     }
     size_t mx = 0;
     for (auto& v : q) {
-        std::stable_sort(v.begin(), v.end(), [](const std::pair<int64_t, int2>& x,
-                                                const std::pair<int64_t, int2>& y) {
+        std::stable_sort(v.begin(), v.end(), [](const std::pair<int64_t, int4>& x,
+                                                const std::pair<int64_t, int4>& y) {
             return x.first > y.first;
         });
         mx = std::max(mx, v.size());
     }
-    std::vector<int2> out;
+    std::vector<int4> out;
     out.reserve(mx * 8);
     for (size_t i = 0; i < mx; i++)
-        for (int x = 0; x < 8; x++) out.push_back(i < q[x].size() ? q[x][i].second : make_int2(-1, 0));
+        for (int x = 0; x < 8; x++) out.push_back(i < q[x].size() ? q[x][i].second : make_int4(-1, 0, 0, 0));
     return out;
 }
 
@@ -674,6 +683,7 @@ static void l0_problem(discover_ctx* ctx, const discover_l0_problem& pb, int D, 
     prep_gram(ctx, pb, L, st);
     const int S = pb.S;
     std::vector<int2> items;
+    std::vector<int4> items3;
     int per = 64;
     if (D == 1) {
         for (int a0 = 0; a0 < S; a0 += 64) items.push_back(make_int2(0, a0));
@@ -681,15 +691,19 @@ static void l0_problem(discover_ctx* ctx, const discover_l0_problem& pb, int D, 
         for (int a = 0; a < S - 1; a++)
             for (int b0 = a + 1; b0 < S; b0 += 64) items.push_back(make_int2(a, b0));
     } else {
-        items = sweep3_blocks(S);
+        items3 = sweep3_blocks(S);
         per = 4 * SW3_A * 64;
     }
-    const int64_t ni = (int64_t)items.size();
+    const int64_t ni = D == 3 ? (int64_t)items3.size() : (int64_t)items.size();
     const int64_t nl = ni * per;
-    int2* d_items = ctx->buf<int2>("l0items", ni);
-    DSC_HIP(hipMemcpyAsync(d_items, items.data(), ni * sizeof(int2), hipMemcpyHostToDevice, st));
+    int2* d_items = ctx->buf<int2>("l0items", D == 3 ? 1 : ni);
+    int4* d_items3 = ctx->buf<int4>("l0items3", D == 3 ? ni : 1);
+    if (D == 3)
+        DSC_HIP(hipMemcpyAsync(d_items3, items3.data(), ni * sizeof(int4), hipMemcpyHostToDevice, st));
+    else
+        DSC_HIP(hipMemcpyAsync(d_items, items.data(), ni * sizeof(int2), hipMemcpyHostToDevice, st));
     SweepArgs g{};
-    g.G = L.G; g.ldg = L.ldg; g.S = S; g.D = D; g.items = d_items; g.n_items = ni;
+    g.G = L.G; g.ldg = L.ldg; g.S = S; g.D = D; g.items = d_items; g.items3 = d_items3; g.n_items = ni;
     g.lane_q = ctx->buf<double>("l0laneq", nl);
     {
         KTimer kt(ctx, st, D == 3 ? "l0_sweep3" : "l0_sweep");
@@ -702,7 +716,8 @@ static void l0_problem(discover_ctx* ctx, const discover_l0_problem& pb, int D, 
     uint32_t* sel = ctx->buf<uint32_t>("l0sel", 4);
     int64_t* sst = ctx->buf<int64_t>("l0selst", 2);
     BandArgs bg{};
-    bg.G = L.G; bg.ldg = L.ldg; bg.S = S; bg.D = D; bg.items = d_items; bg.n_lanes = nl;
+    bg.G = L.G; bg.ldg = L.ldg; bg.S = S; bg.D = D; bg.items = d_items; bg.items3 = d_items3;
+    bg.n_lanes = nl;
     bg.lane_q = g.lane_q; bg.sel = sel; bg.st = sst;
     bg.bcnt = ctx->buf<unsigned long long>("l0bcnt", 2);
     bg.pcnt = bg.bcnt + 1;
@@ -711,7 +726,7 @@ static void l0_problem(discover_ctx* ctx, const discover_l0_problem& pb, int D, 
         bg.bcap = cap;
         bg.pcap = cap;
         bg.band = ctx->buf<int4>("l0band", cap);
-        bg.pairs = ctx->buf<int2>("l0pairs", cap);
+        bg.pairs = ctx->buf<int4>("l0pairs", cap);
         DSC_HIP(hipMemsetAsync(bg.bcnt, 0, 16, st));
         {
             KTimer kt(ctx, st, "l0_band");

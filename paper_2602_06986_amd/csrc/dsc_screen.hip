@@ -1539,23 +1539,31 @@ static void launch_pairs_t(const PairArgs& a, bool list, hipStream_t st) {
 }
 
 template <int OPS>
-static void launch_pairs_ops(const PairArgs& a, bool list, int TP, hipStream_t st) {
+static void launch_pairs_ops(const PairArgs& a, bool list, int TP, int J, hipStream_t st) {
     switch (TP) {
-    case 1: launch_pairs_t<OPS, 4, 1>(a, list, st); break;
-    case 2: launch_pairs_t<OPS, 2, 2>(a, list, st); break;
+    case 1:
+        if (J == 4) launch_pairs_t<OPS, 4, 1>(a, list, st);
+        else if (J == 2) launch_pairs_t<OPS, 2, 1>(a, list, st);
+        else launch_pairs_t<OPS, 1, 1>(a, list, st);
+        break;
+    case 2:
+        if (J == 2) launch_pairs_t<OPS, 2, 2>(a, list, st);
+        else launch_pairs_t<OPS, 1, 2>(a, list, st);
+        break;
     case 4: launch_pairs_t<OPS, 1, 4>(a, list, st); break;
     case 8: launch_pairs_t<OPS, 1, 8>(a, list, st); break;
     default: launch_pairs_t<OPS, 1, 16>(a, list, st); break;
     }
 }
 
-static int dense_J(int TP) { return TP == 1 ? 4 : TP == 2 ? 2 : 1; }
+// Tile widths J (operand features j per wave) the dense kernel is built for.
+static int max_J(int TP) { return TP == 1 ? 4 : TP == 2 ? 2 : 1; }
 
-static void launch_pairs(int OPS, const PairArgs& a, bool list, int TP, hipStream_t st) {
+static void launch_pairs(int OPS, const PairArgs& a, bool list, int TP, int J, hipStream_t st) {
     switch (OPS) {
-    case 31: launch_pairs_ops<31>(a, list, TP, st); break;
-    case 28: launch_pairs_ops<28>(a, list, TP, st); break;
-    case 3: launch_pairs_ops<3>(a, list, TP, st); break;
+    case 31: launch_pairs_ops<31>(a, list, TP, J, st); break;
+    case 28: launch_pairs_ops<28>(a, list, TP, J, st); break;
+    case 3: launch_pairs_ops<3>(a, list, TP, J, st); break;
     default: DSC_FAIL(DISCOVER_E_UNSUPPORTED, "operator class %d", OPS);
     }
 }
@@ -1592,8 +1600,10 @@ struct Plan {
     int32_t *mat_a = nullptr, *mat_b = nullptr;
     ListItem* items = nullptr;
     int64_t n_items = 0;
-    int2* dtiles = nullptr;
-    int64_t n_dtiles = 0;
+    int2* dtilesJ[3] = {nullptr, nullptr, nullptr};   // dense tiles for J = 1, 2, 4
+    int64_t n_dtilesJ[3] = {0, 0, 0};
+    int tuned_J = 0;                                     // 0: not tuned yet
+    double tune_ms[3] = {0, 0, 0};
     uint32_t dense_ops = 0;
     int dense_cls = 0;
     int2* ptiles = nullptr;                   // (j, i0) tiles of one j for the precision form
@@ -1685,14 +1695,17 @@ static std::shared_ptr<Plan> get_plan(discover_ctx* ctx, const discover_problem&
     P->list_ops = units ? (bin & 3u) : 0u;
     P->dense_cls = units ? 28 : 31;
     if (P->dense_ops) {
-        const int J = dense_J(P->TP);
-        std::vector<int2> tiles;
-        for (int32_t j = jc0; j < jc1; j += J) {
-            const int32_t ilim = std::min<int32_t>(i_end, std::min<int32_t>(j + J - 1, jc1 - 1));
-            for (int32_t i0 = 0; i0 < ilim; i0 += 64) tiles.push_back(make_int2(j, i0));
+        for (int jx = 0; jx < 3; jx++) {
+            const int J = 1 << jx;
+            if (J > max_J(P->TP)) break;
+            std::vector<int2> tiles;
+            for (int32_t j = jc0; j < jc1; j += J) {
+                const int32_t ilim = std::min<int32_t>(i_end, std::min<int32_t>(j + J - 1, jc1 - 1));
+                for (int32_t i0 = 0; i0 < ilim; i0 += 64) tiles.push_back(make_int2(j, i0));
+            }
+            P->dtilesJ[jx] = P->up(tiles);
+            P->n_dtilesJ[jx] = (int64_t)tiles.size();
         }
-        P->dtiles = P->up(tiles);
-        P->n_dtiles = (int64_t)tiles.size();
         std::vector<int2> pt;
         for (int32_t j = jc0; j < jc1; j++) {
             const int32_t ilim = std::min<int32_t>(i_end, j);
@@ -1775,6 +1788,7 @@ struct Problem {
     uint8_t* r2v = nullptr;                   // rung-2 operand statistics (streamed rung 3)
     double* r2m = nullptr;
     double* r2q = nullptr;
+    int tile_j = 0;                           // dense pair kernel width used (0: not run)
     EvalCtx ev() const {
         EvalCtx e;
         e.sd = plan->sp.d;
@@ -1899,17 +1913,52 @@ static void screen_problem(discover_ctx* ctx, const discover_problem& pb,
         else launch_lp<false>(pl.dense_cls, a, ylp, ldl, st);
         check_launch("k_screen_lp");
     } else if (pl.dense_ops) {
-        a.tiles = pl.dtiles; a.ilist = nullptr; a.icount = nullptr;
-        a.n_tiles = pl.n_dtiles; a.opmask = pl.dense_ops;
+        a.ilist = nullptr; a.icount = nullptr; a.opmask = pl.dense_ops;
+        Plan& mp = *P.plan;
+        if (prm.tile_j <= 0 && mp.tuned_J == 0) {
+            // autotune the tile width once per plan: every variant writes the same
+            // scores (each candidate's sums run in the same order), so the timing
+            // runs only repeat idempotent stores; the counters they bump are
+            // restored after each run, and the fastest J is cached in the plan
+            unsigned long long* saved = ctx->buf<unsigned long long>("screen_ctr_tune", 4);
+            DSC_HIP(hipMemcpyAsync(saved, ctr, 32, hipMemcpyDeviceToDevice, st));
+            double best = 1e30;
+            for (int jx = 0; jx < 3 && (1 << jx) <= max_J(P.TP); jx++) {
+                a.tiles = mp.dtilesJ[jx];
+                a.n_tiles = mp.n_dtilesJ[jx];
+                hipEvent_t e0 = ctx->event(), e1 = ctx->event();
+                DSC_HIP(hipEventRecord(e0, st));
+                launch_pairs(pl.dense_cls, a, false, P.TP, 1 << jx, st);
+                DSC_HIP(hipEventRecord(e1, st));
+                DSC_HIP(hipMemcpyAsync(ctr, saved, 32, hipMemcpyDeviceToDevice, st));
+                DSC_HIP(hipEventSynchronize(e1));
+                float ms = 0.f;
+                DSC_HIP(hipEventElapsedTime(&ms, e0, e1));
+                ctx->free_events.push_back(e0);
+                ctx->free_events.push_back(e1);
+                mp.tune_ms[jx] = ms;
+                if (ms < best) { best = ms; mp.tuned_J = 1 << jx; }
+            }
+        }
+        int J = mp.tuned_J;
+        if (prm.tile_j > 0) {
+            // caller-forced width, rounded down to a power of two built for this TP
+            J = 1;
+            while (J * 2 <= std::min(prm.tile_j, max_J(P.TP))) J *= 2;
+        }
+        P.tile_j = J;
+        const int jx = J == 4 ? 2 : J == 2 ? 1 : 0;
+        a.tiles = mp.dtilesJ[jx];
+        a.n_tiles = mp.n_dtilesJ[jx];
         KTimer kt(ctx, st, "screen_pairs");
-        launch_pairs(pl.dense_cls, a, false, P.TP, st);
+        launch_pairs(pl.dense_cls, a, false, P.TP, J, st);
         check_launch("k_screen_pairs");
     }
     if (pl.list_ops && pl.n_ltiles) {
         a.tiles = pl.ltiles; a.ilist = pl.ilist; a.icount = pl.icount;
         a.n_tiles = pl.n_ltiles; a.opmask = pl.list_ops;
         KTimer kt(ctx, st, "screen_pairs_list");
-        launch_pairs(3, a, true, P.TP, st);
+        launch_pairs(3, a, true, P.TP, 1, st);
         check_launch("k_screen_pairs(list)");
     }
     const EvalCtx ev = P.ev();
@@ -2079,6 +2128,7 @@ static void validate(const discover_problem* probs, int32_t nb, const discover_s
                 "score_mode %d", prm->score_mode);
     DSC_REQUIRE(prm->precision >= DISCOVER_FP64 && prm->precision <= DISCOVER_FP16_GUARD,
                 "precision %d", prm->precision);
+    DSC_REQUIRE(prm->tile_j >= 0 && prm->tile_j <= 4, "tile_j %d outside 0..4", prm->tile_j);
     for (int r = 1; r <= prm->rung; r++) {
         DSC_REQUIRE((prm->rung_ops[r] & ~DISCOVER_OPS_ALL) == 0, "unknown operator bits at rung %d", r);
         DSC_REQUIRE(prm->rung_pool[r] >= -1 && prm->rung_pool[r] < r, "rung_pool[%d]", r);
@@ -2119,6 +2169,7 @@ extern "C" discover_status discover_generate_screen(discover_ctx* ctx, const dis
             screen_problem(ctx, pb, *prm, P, st);
             stats.n_raw = P.plan->sp.n_raw();
             stats.n_unit_valid = P.plan->sp.n_unit_valid;
+            stats.tile_j = P.tile_j;
             double margin = 4.0 * P.n * EPS64 * KAPPA_MAX;
             if (prm->precision != DISCOVER_FP64) {
                 stats.guard_band = lowprec_delta(prm->precision, P.n);

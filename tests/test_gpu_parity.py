@@ -178,6 +178,30 @@ def test_screen_random(torch, ctx, D, oracle_mod, seed, p, n, B, R, dedup, k):
         assert bool((ids[0][n_sel:] == -1).all())
 
 
+@pytest.mark.parametrize("T", [1, 2, 3])
+def test_tile_width_invariant(torch, ctx, D, T):
+    """The dense pair kernel's tile width (forced 1/2/4, or autotuned) does
+    not change a single bit of the scores or the selection."""
+    rng = np.random.default_rng(77 + T)
+    p, n = 11, 203
+    X = rng.lognormal(0, 0.5, size=(p, n))
+    Y = np.stack([X[t] * X[-1 - t] + 0.1 * rng.normal(size=n) for t in range(T)])
+    Xd, Yd = dev(torch, X), dev(torch, Y)
+    runs = {}
+    for tj in (0, 1, 2, 4):
+        ids, sc, vals, st = ctx.generate_screen(Xd, Yd, D.params(rung=2, k=60, tile_j=tj))
+        runs[tj] = (ids.cpu().numpy(), sc.cpu().numpy(), st["tile_j"])
+    widest = {1: 4, 2: 2}.get(T, 1)
+    for tj in (1, 2, 4):
+        assert runs[tj][2] == min(tj, widest)
+        assert np.array_equal(runs[tj][0], runs[1][0])
+        assert np.array_equal(runs[tj][1].view(np.int64), runs[1][1].view(np.int64))
+    assert runs[0][2] in (1, 2, 4) and runs[0][2] <= widest
+    assert np.array_equal(runs[0][0], runs[1][0])
+    with pytest.raises(D.DiscoverError):
+        ctx.generate_screen(Xd, Yd, D.params(rung=2, k=60, tile_j=5))
+
+
 def test_screen_exclusion(torch, ctx, D, oracle_mod):
     """IDs already in the subspace and their duplicate groups are not
     selected again."""
