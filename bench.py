@@ -26,6 +26,29 @@ sys.path.insert(0, ROOT)
 PEAK_FP64 = 78.6e12          # MI355X FP64 vector, FLOP/s
 L0_FLOP_PER_SUBSET = 10      # Schur rank-1 extension per 3-subset
 
+# HBM bytes of one k_sweep3 launch on this workload, from rocprofv3 FETCH_SIZE /
+# WRITE_SIZE passes (KiB per dispatch) scaled by what the same counters read for a
+# plain 1 GiB device copy.  Valid only for the kernel source they were taken on.
+SWEEP3_COUNTERS = {
+    "source": "paper_2602_06986_amd/csrc/dsc_l0.hip",
+    "sha256": "81d4fd43c9a0aacea622f417d4f37c16d6df1924792cb47e8347d479a19ef776",
+    "fetch_kib": 41468.9, "fetch_scale": 1.9999,
+    "write_kib": 25600.0, "write_scale": 1.0,
+}
+
+
+def sweep3_traffic():
+    """Scaled counter bytes per launch, or None once the kernel source differs."""
+    import hashlib
+    c = SWEEP3_COUNTERS
+    try:
+        with open(os.path.join(ROOT, c["source"]), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != c["sha256"]:
+                return None
+    except OSError:
+        return None
+    return (c["fetch_kib"] * c["fetch_scale"] + c["write_kib"] * c["write_scale"]) * 1024.0
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -33,6 +56,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-oracle", action="store_true", help="skip the parity gate and CPU baseline")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run one plain device-to-device copy of MIB MiB (the reference "
+                         "kernel that scales HBM byte counters)")
     return ap.parse_args()
 
 
@@ -71,6 +97,13 @@ def main():
     prm = Dm.params(ops=w["ops"], rung=w["rung"], k=w["k"])
     ctx = Dm.Context(0)
     omp_D = 6
+
+    if args.copy_calibration:
+        src = torch.ones(args.copy_calibration << 17, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def step():
         return ctx.sisso(X, y, prm, w["D"], units=w["units"], n_resid=w["n_resid"], omp_D=omp_D)
@@ -112,7 +145,7 @@ def main():
         ach = flops / (dom["avg_ms"] * 1e-3)
         roofline = {"kernel": "k_sweep3 (L0 D=3 sweep)", "bound": "alu", "achieved": ach / 1e12,
                     "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": ach / PEAK_FP64,
-                    "traffic": None}
+                    "traffic": sweep3_traffic()}
     line = {
         "metric": "candidates screened/s + L0 subsets fitted/s, exact top-k vs FP64 oracle",
         "value": value, "unit": "items/s", "n_gpus": 1, "steps": args.steps,
