@@ -21,6 +21,7 @@ namespace dsc {
 
 constexpr double PIV_TOL = 1e-10;     // normalized Cholesky pivot at/below which a subset is singular
 constexpr double GRAM_DELTA = 1e-7;   // band width in explained fraction
+constexpr double SW3_RCP_DELTA = 4.76837158203125e-7;  // 2^-21: D = 3 sweep values use a bare rcp
 constexpr double TAU_TIE = 1e-11;     // RSS tie tolerance relative to ||y - mean||^2
 
 // ------------------------------------------------------------------ prep
@@ -97,23 +98,19 @@ __global__ __launch_bounds__(256) void k_gram(int M, int ldz, int nk, const doub
 // ----------------------------------------------------------------- sweep
 // Every sweep writes, per lane, the best explained fraction q of the
 // subsets that lane owns (D = 1, 2: exactly one subset per lane; D = 3: the
-// lane's (a, c) pair over all b, with b packed into the low 16 mantissa
-// bits).  A radix selection over these lane values gives the m-th best, and
-// only lanes reaching the band threshold are expanded again.
+// lane's (a, c) pair over its block's range of b).  A radix selection over
+// these lane values gives the m-th best, and only lanes reaching the band
+// threshold are expanded again.
 struct SweepArgs {
     const double* G;
     int ldg, S, D;
+    const double4* E;         // D = 3: (a, b) factor table, E[b * lde + a]
+    int lde;
     const int2* items;        // D = 1, 2: (a, first b) per wave
     const int4* items3;       // D = 3: (a0, c0, b_lo, b_hi) per block
     int64_t n_items;
     double* lane_q;           // [n_items][64] (D = 1, 2) or [n_items][256] (D = 3)
 };
-
-__device__ __forceinline__ double pack_q(double q, int b) {
-    unsigned long long u = (unsigned long long)__double_as_longlong(q);
-    u = (u & ~0xFFFFull) | (unsigned long long)(b & 0xFFFF);
-    return __longlong_as_double((long long)u);
-}
 
 __device__ __forceinline__ double fast_rcp(double x) {
     double r = __builtin_amdgcn_rcp(x);
@@ -156,16 +153,20 @@ __global__ __launch_bounds__(256) void k_sweep2(SweepArgs g) {
 }
 
 // D = 3.  One block = 16 consecutive a (4 per wave) x 64 consecutive c (one
-// per lane), looping over b.  Each G[b][c] load serves the wave's 4 values
-// of a.  Per (a, b) (uniform, staged in LDS): u_b = G[a][b],
+// per lane) x a range of b.  Each G[b][c] load serves the wave's 4 values
+// of a.  Per (a, b), the same for every lane of a wave: u_b = G[a][b],
 // g_b = z'_b / d_b, h_b = 1 / d_b, Q_ab = c_a^2 / G_aa + z'_b^2 / d_b with
 // d_b = G_bb - u_b^2 / G_aa and z'_b = c_b - u_b c_a / G_aa.  Per subset:
 //   C'  = G[b][c] - u_b u_c / G_aa
 //   den = d_c - C'^2 / d_b            (third Cholesky pivot)
 //   e   = z'_c - C' g_b
 //   q   = Q_ab + e^2 / den.
+// The (a, b) factors are tabulated once per call, b-major (E[b][a]), so a
+// wave's four entries for one b are 128 contiguous bytes at a wave-uniform
+// address: they arrive through scalar loads into SGPRs and enter the FP64
+// FMAs as scalar operands, leaving LDS and the vector memory path to the
+// per-lane G[b][c] stream.
 constexpr int SW3_A = 4;              // values of a per wave
-constexpr int SW3_CHUNK = 64;         // b entries staged per a and chunk (16 x 64 x 32 B = 32 KB)
 
 struct Sw3Lane {
     double upc, dc, zc;
@@ -192,85 +193,126 @@ __device__ __forceinline__ double sw3_q(const double4& e, const Sw3Lane& L, doub
     return fma(ee * ee, fast_rcp(den), e.w);
 }
 
+// Table of (a, b) factors, E[b * lde + a], lde >= S + 16.  Row b holds every
+// a < b and the entries a = b .. b + 15 that a block starting below b may
+// also read (a wave's a values reach at most 15 past the block's first a).
+// Entries that cannot form a triple (b <= a, a >= S - 2, a or the pair
+// (a, b) singular) carry h_b = NaN: den is then NaN and fails the pivot
+// test for every c.
+__global__ __launch_bounds__(256) void k_sw3_table(const double* __restrict__ G, int ldg, int S,
+                                                   double4* __restrict__ E, int lde) {
+    const int b = blockIdx.y;
+    const int a = blockIdx.x * 256 + threadIdx.x;
+    if (a >= lde || a > b + 15) return;
+    double4 e = make_double4(0.0, 0.0, __builtin_nan(""), 0.0);
+    if (a < S - 2 && b > a) {
+        const double* Ga = G + (int64_t)a * ldg;
+        const double caa = Ga[a];
+        if (caa > PIV_TOL) {
+            const double4 f = sw3_b_entry(G, ldg, S, Ga, 1.0 / caa, Ga[S], b);
+            if (f.w >= 0.0) e = f;
+        }
+    }
+    E[(int64_t)b * lde + a] = e;
+}
+
+// min(low, ok ? x : +huge): the mask selects only the high word (a value
+// with high word 0x7FEFFFFF is a large positive finite number whatever its
+// low word), and the minimum is one v_min_f64.  Both operands are ordinary
+// finite numbers, so the input quieting the compiler adds around fmin (for
+// signalling NaNs) is not needed; the instruction is written out to leave it
+// out.  Its inputs come from plain VALU instructions, never from a
+// transcendental one.
+__device__ __forceinline__ double sw3_keep(double low, double x, bool ok) {
+    const int hi = ok ? __double2hiint(x) : (int)0x7FEFFFFF;
+    const double v = __hiloint2double(hi, __double2loint(x));
+    double r;
+    asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(low), "v"(v));
+    return r;
+}
+
+// The sweep's own value, -q~ with q~ = e^2 * rcp(den) + Q_ab, where rcp is
+// the bare hardware reciprocal (relative error below 2^-24 measured on
+// gfx950; SW3_RCP_DELTA allows 2^-21 of the explained fraction).  The
+// negated form keeps Q_ab a wave-uniform SGPR operand of one VOP3 FMA
+// (a negated addend cannot use the accumulating VOP2 form, which would need
+// Q_ab copied into VGPRs); the lanes track the minimum of -q~.
+__device__ __forceinline__ double sw3_negq(const double4& e, const Sw3Lane& L, double Cbc,
+                                           double& den) {
+    const double Cp = fma(-e.x, L.upc, Cbc);
+    const double ee = fma(-Cp, e.y, L.zc);
+    const double t = Cp * e.z;
+    den = fma(-Cp, t, L.dc);
+    return fma(-(ee * ee), __builtin_amdgcn_rcp(den), -e.w);
+}
+
+template <bool DIAG>
+__device__ __forceinline__ void sw3_run(const double4* __restrict__ Ew, int lde, const double* colc,
+                                        int ldg, int S, int c, int b, int bend,
+                                        const Sw3Lane (&L)[SW3_A], double (&low)[SW3_A]) {
+    if (b >= bend) return;
+    double Cnext = colc[(int64_t)b * ldg];
+    for (; b < bend; b++) {
+        double Cbc = Cnext;
+        Cnext = colc[(int64_t)min(b + 1, S - 1) * ldg];
+        if (DIAG && b >= c) Cbc = __builtin_nan("");    // lanes with c <= b own no triple here
+        const double4* Eb = Ew + (int64_t)b * lde;
+#pragma unroll
+        for (int k = 0; k < SW3_A; k++) {
+            const double4 e = Eb[k];
+            double den;
+            const double nq = sw3_negq(e, L[k], Cbc, den);
+            low[k] = sw3_keep(low[k], nq, den > PIV_TOL);
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void k_sweep3(SweepArgs g) {
-    __shared__ double4 tab[4 * SW3_A][SW3_CHUNK];
     const int4 item = g.items3[blockIdx.x];
     const int a0 = item.x, c0 = item.y;                  // block: a0..a0+15, c0..c0+63, b in [z, w)
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     const int c = c0 + lane;
     double* out = g.lane_q + ((int64_t)blockIdx.x * 4 + wv) * (SW3_A * 64);
     if (a0 < 0) {                                        // padding block (uniform)
         for (int k = 0; k < SW3_A; k++) out[k * 64 + lane] = -1.0;
         return;
     }
+    const int aw = a0 + wv * SW3_A;                      // the wave's first a
     const bool cok = c < g.S;
     const int cc = cok ? c : g.S - 1;
     const double Gcc = g.G[(int64_t)cc * g.ldg + cc], cyc = g.G[(int64_t)cc * g.ldg + g.S];
     Sw3Lane L[SW3_A];
-    double best[SW3_A];
-    int av[SW3_A];
-    bool aok[SW3_A];
+    double low[SW3_A];                                   // min over b of -q~
 #pragma unroll
     for (int k = 0; k < SW3_A; k++) {
-        const int a = a0 + wv * SW3_A + k;
-        av[k] = a;
-        const int ac = a < g.S ? a : g.S - 1;
+        const int ac = min(aw + k, g.S - 1);
         const double* Ga = g.G + (int64_t)ac * g.ldg;
         const double caa = Ga[ac], ca = Ga[g.S];
-        aok[k] = a < g.S - 2 && caa > PIV_TOL;
-        const double ica = 1.0 / caa;
-        const double uc = Ga[cc];
-        L[k].upc = uc * ica;
-        L[k].dc = Gcc - uc * L[k].upc;
-        L[k].zc = cyc - ca * L[k].upc;
-        best[k] = -1.0;
+        const double upc = Ga[cc] * (1.0 / caa);
+        L[k].upc = upc;
+        // an out-of-range c makes den NaN, so none of its triples passes
+        L[k].dc = cok ? Gcc - Ga[cc] * upc : __builtin_nan("");
+        L[k].zc = cyc - ca * upc;
+        low[k] = 1.0;
     }
     const double* colc = g.G + cc;
+    const double4* Ew = g.E + aw;
+    const int bstart = max(aw + 1, item.z);
     const int bend = min(min(g.S - 1, c0 + 63), item.w); // b < largest c of the block
-    for (int b0 = max(a0 + 1, item.z); b0 < bend; b0 += SW3_CHUNK) {
-        const int nb = min(SW3_CHUNK, bend - b0);
-        __syncthreads();
-        // stage (a, b) factors for the block's 16 values of a
-        for (int t = threadIdx.x; t < 4 * SW3_A * nb; t += 256) {
-            const int ka = t / nb, bb = b0 + t % nb;
-            const int a = a0 + ka;
-            double4 e = make_double4(0.0, 0.0, 0.0, -INFINITY);   // b <= a or singular: q = -inf
-            if (a < g.S - 2 && bb > a) {
-                const double* Ga = g.G + (int64_t)a * g.ldg;
-                const double caa = Ga[a];
-                if (caa > PIV_TOL) {
-                    e = sw3_b_entry(g.G, g.ldg, g.S, Ga, 1.0 / caa, Ga[g.S], bb);
-                    if (e.w < 0.0) e.w = -INFINITY;
-                }
-            }
-            tab[ka][t % nb] = e;
-        }
-        __syncthreads();
-        // branch-free inner loop; G[b][c] of the next b is loaded ahead
-        double Cnext = colc[(int64_t)b0 * g.ldg];
-        for (int b = b0; b < b0 + nb; b++) {
-            const double Cbc = Cnext;
-            Cnext = colc[(int64_t)min(b + 1, g.S - 1) * g.ldg];
-            const bool bc = cok && b < c;
+    // b < c0: every lane has c > b; from c0 on, lanes with c <= b are masked
+    sw3_run<false>(Ew, g.lde, colc, g.ldg, g.S, c, bstart, min(bend, c0), L, low);
+    sw3_run<true>(Ew, g.lde, colc, g.ldg, g.S, c, max(bstart, c0), bend, L, low);
 #pragma unroll
-            for (int k = 0; k < SW3_A; k++) {
-                const double4 e = tab[wv * SW3_A + k][b - b0];
-                double den;
-                const double q = sw3_q(e, L[k], Cbc, den);
-                const double v = (bc && den > PIV_TOL) ? q : -INFINITY;
-                best[k] = v > best[k] ? v : best[k];
-            }
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < SW3_A; k++) out[k * 64 + lane] = best[k];
-    (void)av;
+    for (int k = 0; k < SW3_A; k++) out[k * 64 + lane] = -low[k];   // -1: no valid triple
 }
 
 // Band expansion.  thr = (m-th best lane value) * (1 - 1e-12) - GRAM_DELTA.
 struct BandArgs {
     const double* G;
     int ldg, S, D;
+    const double4* E;         // D = 3 factor table (as in SweepArgs)
+    int lde;
     const int2* items;
     int64_t n_lanes;
     const double* lane_q;
@@ -285,9 +327,15 @@ struct BandArgs {
     int64_t pcap;
 };
 
+// For D = 3 the lane values carry the sweep's reciprocal error (at most
+// SW3_RCP_DELTA): the m lanes at or above the selected value hold m distinct
+// subsets whose exact q is at least that value minus SW3_RCP_DELTA, so the
+// threshold drops by it; and a lane whose exact best reaches the threshold
+// shows a sweep value no lower than threshold - SW3_RCP_DELTA.
 __device__ __forceinline__ double band_thr(const BandArgs& g) {
     if (g.st[1]) return -0.5;                            // fewer than m valid lanes: take all
-    return select_threshold(g.sel, g.st) * (1.0 - 1e-12) - GRAM_DELTA;
+    return select_threshold(g.sel, g.st) * (1.0 - 1e-12) - GRAM_DELTA -
+           (g.D == 3 ? SW3_RCP_DELTA : 0.0);
 }
 
 __device__ __forceinline__ void band_push(const BandArgs& g, int a, int b, int c) {
@@ -301,7 +349,7 @@ __global__ __launch_bounds__(256) void k_band_lanes(BandArgs g) {
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < g.n_lanes;
          i += (int64_t)gridDim.x * 256) {
         const double q = g.lane_q[i];
-        if (!(q > -0.5) || q < thr - 1e-9) continue;
+        if (!(q > -0.5) || q < thr - (g.D == 3 ? SW3_RCP_DELTA : 0.0) - 1e-9) continue;
         const int lane = (int)(i % per);
         if (g.D == 1) band_push(g, g.items[i / per].y + lane, -1, -1);
         else if (g.D == 2) band_push(g, g.items[i / per].x, g.items[i / per].y + lane, -1);
@@ -325,15 +373,13 @@ __global__ __launch_bounds__(256) void k_band_expand3(BandArgs g) {
         const int blo = max(a + 1, g.pairs[i].z), bhi = min(c, g.pairs[i].w);
         const double* Ga = g.G + (int64_t)a * g.ldg;
         const double caa = Ga[a], ca = Ga[g.S];
-        const double ica = 1.0 / caa;
-        Sw3Lane L;
+        Sw3Lane L;                                       // the same arithmetic as the sweep
         const double uc = Ga[c];
-        L.upc = uc * ica;
+        L.upc = uc * (1.0 / caa);
         L.dc = g.G[(int64_t)c * g.ldg + c] - uc * L.upc;
         L.zc = g.G[(int64_t)c * g.ldg + g.S] - ca * L.upc;
         for (int b = blo + lane; b < bhi; b += 64) {
-            const double4 e = sw3_b_entry(g.G, g.ldg, g.S, Ga, ica, ca, b);
-            if (e.w < 0.0) continue;
+            const double4 e = g.E[(int64_t)b * g.lde + a];
             double den;
             const double q = sw3_q(e, L, g.G[(int64_t)b * g.ldg + c], den);
             if (den > PIV_TOL && q >= thr) band_push(g, a, b, c);
@@ -705,6 +751,15 @@ static void l0_problem(discover_ctx* ctx, const discover_l0_problem& pb, int D, 
     SweepArgs g{};
     g.G = L.G; g.ldg = L.ldg; g.S = S; g.D = D; g.items = d_items; g.items3 = d_items3; g.n_items = ni;
     g.lane_q = ctx->buf<double>("l0laneq", nl);
+    if (D == 3) {
+        g.lde = (int)cdiv(S + 16, 4) * 4;
+        double4* E = ctx->buf<double4>("l0sw3tab", (size_t)S * g.lde);
+        g.E = E;
+        KTimer kt(ctx, st, "l0_table");
+        dim3 gt((unsigned)cdiv(g.lde, 256), (unsigned)S);
+        k_sw3_table<<<gt, 256, 0, st>>>(L.G, L.ldg, S, E, g.lde);
+        check_launch("k_sw3_table");
+    }
     {
         KTimer kt(ctx, st, D == 3 ? "l0_sweep3" : "l0_sweep");
         if (D == 1) k_sweep1<<<(unsigned)cdiv(ni, 4), 256, 0, st>>>(g);
@@ -717,6 +772,7 @@ static void l0_problem(discover_ctx* ctx, const discover_l0_problem& pb, int D, 
     int64_t* sst = ctx->buf<int64_t>("l0selst", 2);
     BandArgs bg{};
     bg.G = L.G; bg.ldg = L.ldg; bg.S = S; bg.D = D; bg.items = d_items; bg.items3 = d_items3;
+    bg.E = g.E; bg.lde = g.lde;
     bg.n_lanes = nl;
     bg.lane_q = g.lane_q; bg.sel = sel; bg.st = sst;
     bg.bcnt = ctx->buf<unsigned long long>("l0bcnt", 2);
