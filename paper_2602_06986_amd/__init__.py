@@ -215,6 +215,83 @@ class Context:
             _stream_handle(torch, dev)))
         return ids, sc, vals, st.asdict()
 
+    def generate_screen_batch(self, Xs, Ys, prm, units=None, excludes=None, values=True):
+        """One call over many datasets: Xs[b] [p_b][n_b], Ys[b] [T_b][n_b]
+        float64 CUDA tensors; units[b] host [p_b][B] int32 or None;
+        excludes[b] int64 CUDA tensor or None.  Returns per-dataset lists
+        (ids [T'_b][k], scores, values [T'_b][k][n_max] or None, stats)."""
+        torch = self.torch
+        import numpy as np
+        nb = len(Xs)
+        Xs = [x.contiguous() for x in Xs]
+        Ys = [y.contiguous() for y in Ys]
+        dev = Xs[0].device
+        tl = [1 if prm.score_mode == SCORE_MAX else y.shape[0] for y in Ys]
+        rows = sum(tl)
+        nmax = max(x.shape[1] for x in Xs)
+        ids = torch.empty((rows, prm.k), dtype=torch.int64, device=dev)
+        sc = torch.empty((rows, prm.k), dtype=torch.float64, device=dev)
+        vals = torch.empty((rows, prm.k, nmax), dtype=torch.float64, device=dev) if values else None
+        pbs = (Problem * nb)()
+        keep = []
+        for b in range(nb):
+            pb = pbs[b]
+            p_, n_ = Xs[b].shape
+            pb.n, pb.p, pb.T = n_, p_, Ys[b].shape[0]
+            u = units[b] if units is not None else None
+            if u is not None:
+                u = np.ascontiguousarray(u, dtype=np.int32)
+                keep.append(u)
+                pb.B, pb.units = u.shape[1], u.ctypes.data
+            else:
+                pb.B = 0
+            pb.X, pb.ldx = Xs[b].data_ptr(), n_
+            pb.Y, pb.ldy = Ys[b].data_ptr(), n_
+            e = excludes[b] if excludes is not None else None
+            if e is not None and e.numel():
+                e = e.contiguous()
+                keep.append(e)
+                pb.exclude, pb.n_exclude = e.data_ptr(), e.numel()
+        st = (ScreenStats * nb)()
+        _check(lib().discover_generate_screen(
+            self.h, pbs, nb, C.byref(prm), ids.data_ptr(), sc.data_ptr(),
+            vals.data_ptr() if vals is not None else None, nmax, st, _stream_handle(torch, dev)))
+        out, r = [], 0
+        for b in range(nb):
+            out.append((ids[r:r + tl[b]], sc[r:r + tl[b]],
+                        vals[r:r + tl[b], :, :Xs[b].shape[1]] if vals is not None else None,
+                        st[b].asdict()))
+            r += tl[b]
+        return out
+
+    def l0_fit_batch(self, Fs, idss, ys, D, m=1, resid=True):
+        """Exhaustive L0 of many subspaces in one call: Fs[b] [S_b][n_b],
+        idss[b] [S_b] int64, ys[b] [n_b] (CUDA).  Returns per-dataset lists
+        (subsets [m][D], rmse [m], coef [m][D+1], resid [m][n_b] or None, stats)."""
+        torch = self.torch
+        nb = len(Fs)
+        Fs = [f.contiguous() for f in Fs]
+        idss = [i.contiguous() for i in idss]
+        ys = [y.contiguous() for y in ys]
+        dev = Fs[0].device
+        nmax = max(f.shape[1] for f in Fs)
+        sub = torch.empty((nb, m, D), dtype=torch.int32, device=dev)
+        rmse = torch.empty((nb, m), dtype=torch.float64, device=dev)
+        coef = torch.empty((nb, m, D + 1), dtype=torch.float64, device=dev)
+        res = torch.empty((nb, m, nmax), dtype=torch.float64, device=dev) if resid else None
+        pbs = (L0Problem * nb)()
+        for b in range(nb):
+            S, n = Fs[b].shape
+            pbs[b].n, pbs[b].S, pbs[b].F, pbs[b].ldf = n, S, Fs[b].data_ptr(), n
+            pbs[b].ids, pbs[b].y = idss[b].data_ptr(), ys[b].data_ptr()
+        st = (L0Stats * nb)()
+        _check(lib().discover_l0_fit(self.h, pbs, nb, D, m, sub.data_ptr(), rmse.data_ptr(),
+                                     coef.data_ptr(), res.data_ptr() if res is not None else None,
+                                     nmax, st, _stream_handle(torch, dev)))
+        return [(sub[b], rmse[b], coef[b],
+                 res[b, :, :Fs[b].shape[1]] if res is not None else None, st[b].asdict())
+                for b in range(nb)]
+
     def l0_fit(self, F, ids, y, D, m=1, resid=True):
         """F [S][n] float64, ids [S] int64, y [n] float64 (CUDA).  Returns
         (subsets [m][D] rows, rmse [m], coef [m][D+1], resid [m][n], stats)."""
@@ -266,6 +343,36 @@ class Context:
         return act, coef, rmse, res
 
     # ------------------------------------------------------------ loop
+    def sisso_batch(self, Xs, ys, prm, D, n_resid=1):
+        """The SISSO loop over many datasets at once: every dimension is one
+        batched screening call and one batched L0 call.  Returns one result
+        dict per dataset, shaped like ``sisso``'s."""
+        torch = self.torch
+        nb = len(Xs)
+        dev = Xs[0].device
+        S_ids = [torch.zeros(0, dtype=torch.int64, device=dev) for _ in range(nb)]
+        F = [torch.zeros((0, x.shape[1]), dtype=torch.float64, device=dev) for x in Xs]
+        targets = [y.reshape(1, -1) for y in ys]
+        dims = [[] for _ in range(nb)]
+        for d in range(1, D + 1):
+            q = ScreenParams.from_buffer_copy(prm)
+            if n_resid > 1 and d > 1:
+                q.score_mode = SCORE_MAX
+            scr = self.generate_screen_batch(Xs, targets, q, excludes=S_ids)
+            for b in range(nb):
+                ids, sc, vals, st = scr[b]
+                ok = ids[0] >= 0
+                S_ids[b] = torch.cat([S_ids[b], ids[0][ok]])
+                F[b] = torch.cat([F[b], vals[0][ok]])
+            fits = self.l0_fit_batch(F, S_ids, ys, d, n_resid)
+            for b in range(nb):
+                sub, rmse, coef, res, l0st = fits[b]
+                ids, sc, vals, st = scr[b]
+                dims[b].append({"sel_ids": ids[0], "sel_scores": sc[0], "screen_stats": st,
+                                "subsets": sub, "rmse": rmse, "coef": coef, "l0_stats": l0st})
+            targets = [fits[b][3] for b in range(nb)]
+        return [{"dims": dims[b], "S_ids": S_ids[b], "F": F[b]} for b in range(nb)]
+
     def sisso(self, X, y, prm, D, units=None, n_resid=1, omp_D=0):
         """The SISSO loop: for d = 1..D screen against the residual(s) of the
         best dimension-(d-1) model(s) (the target at d = 1), append the k

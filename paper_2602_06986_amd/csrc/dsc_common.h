@@ -9,6 +9,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <map>
 #include <memory>
 #include <string>
@@ -84,12 +85,22 @@ struct discover_ctx {
     std::vector<Pending> pending;
     std::vector<hipEvent_t> free_events;
     std::map<std::string, std::shared_ptr<void>> plans;   // cached search-space plans
+    std::map<std::string, std::shared_ptr<void>> batches; // cached batch plans / graphs
+    std::map<std::string, std::vector<char>> shadows;     // host copies of uploaded arguments
+    std::map<std::string, int> tuned;                     // autotuned tile choices
+    // While a launch sequence is being captured into a graph nothing may
+    // allocate, synchronise or copy from the host: buffers must already be
+    // large enough and argument tables already uploaded.
+    bool capturing = false;
 
     // Grow-only named device buffer of at least `bytes` bytes.
     void* raw(const std::string& name, size_t bytes) {
         Buf& b = bufs[name];
         if (bytes == 0) bytes = 256;
         if (b.cap < bytes) {
+            if (capturing)
+                DSC_FAIL(DISCOVER_E_CAPACITY, "buffer %s would grow during graph capture",
+                         name.c_str());
             if (b.p) {
                 hipError_t e = hipFree(b.p);
                 (void)e;
@@ -111,6 +122,30 @@ struct discover_ctx {
     T* buf(const std::string& name, size_t count) {
         return static_cast<T*>(raw(name, count * sizeof(T)));
     }
+
+    // Device copy of a host argument table.  The copy is skipped when the
+    // device buffer already holds exactly these bytes (so a captured
+    // sequence reuses the tables of the eager run that preceded it).
+    void* upload(const std::string& name, const void* data, size_t bytes, hipStream_t st) {
+        void* d = raw(name, bytes);
+        std::vector<char>& sh = shadows[name];
+        const bool same = sh.size() == bytes && bytes && std::memcmp(sh.data(), data, bytes) == 0 &&
+                          shadow_ptr[name] == d;
+        if (!same) {
+            if (capturing)
+                DSC_FAIL(DISCOVER_E_CAPACITY, "argument table %s changed during graph capture",
+                         name.c_str());
+            if (bytes) DSC_HIP(hipMemcpyAsync(d, data, bytes, hipMemcpyHostToDevice, st));
+            sh.assign((const char*)data, (const char*)data + bytes);
+            shadow_ptr[name] = d;
+        }
+        return d;
+    }
+    template <class T>
+    T* upload(const std::string& name, const std::vector<T>& v, hipStream_t st) {
+        return static_cast<T*>(upload(name, v.data(), v.size() * sizeof(T), st));
+    }
+    std::map<std::string, void*> shadow_ptr;
 
     hipEvent_t event() {
         if (!free_events.empty()) {
@@ -147,7 +182,7 @@ struct KTimer {
     const char* name;
     hipEvent_t a = nullptr, b = nullptr;
     KTimer(discover_ctx* c_, hipStream_t s_, const char* n) : c(c_), s(s_), name(n) {
-        if (c->timing) {
+        if (c->timing && !c->capturing) {
             a = c->event();
             b = c->event();
             DSC_HIP(hipEventRecord(a, s));
@@ -182,5 +217,77 @@ __device__ __forceinline__ double wave_max(double v) {
 }
 
 __host__ __device__ __forceinline__ int64_t choose2(int64_t m) { return m * (m - 1) / 2; }
+
+// ------------------------------------------------------ argument tables
+// Per-problem argument tables live in device memory and are read through
+// the constant address space, as kernel arguments are: uniform fields become
+// scalar loads, and structures indexed with run-time subscripts (the search
+// space description) are read in place rather than copied to scratch.
+template <class T>
+using ctab = const __attribute__((address_space(4))) T*;
+
+template <class T>
+inline ctab<T> ct(const T* p) { return (ctab<T>)p; }
+
+template <class T>
+__device__ __forceinline__ const T& tab(ctab<T> A, int64_t i) { return *(const T*)(A + i); }
+
+// Pointers read from a table are generic; this tells the compiler that one
+// addresses global memory (not LDS or scratch), so that it emits global
+// rather than flat memory instructions.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define DSC_GLOBAL(p)                                                                         \
+    __builtin_assume(!__builtin_amdgcn_is_shared((const void*)(p)) &&                          \
+                     !__builtin_amdgcn_is_private((const void*)(p)))
+#else
+#define DSC_GLOBAL(p) ((void)0)   // the host pass does not generate device code
+#endif
+
+// ------------------------------------------------------------ fills
+// Device-side fills of many buffers in one launch (used instead of
+// hipMemsetAsync so that the sequence can be captured into a graph).
+struct FillSeg {
+    void* p;
+    int64_t n32;      // 32-bit words
+    uint32_t v;
+    uint32_t pad;
+};
+
+static __global__ __launch_bounds__(256) void k_fill(ctab<FillSeg> segs) {
+    const FillSeg& f = tab(segs, blockIdx.y);
+    uint32_t* p = (uint32_t*)f.p;
+    DSC_GLOBAL(p);
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < f.n32; i += (int64_t)gridDim.x * 256)
+        p[i] = f.v;
+}
+
+// Launch the fills of `segs` (each size a multiple of 4 bytes).
+inline void fill_all(discover_ctx* ctx, const std::string& name, const std::vector<FillSeg>& segs,
+                     hipStream_t st) {
+    if (segs.empty()) return;
+    int64_t mx = 1;
+    for (const FillSeg& f : segs) mx = std::max<int64_t>(mx, f.n32);
+    const FillSeg* d = ctx->upload(name, segs, st);
+    dim3 g((unsigned)std::min<int64_t>(256, cdiv(mx, 256)), (unsigned)segs.size());
+    k_fill<<<g, 256, 0, st>>>(ct(d));
+    check_launch("k_fill");
+}
+
+inline FillSeg fill_seg(void* p, size_t bytes, uint32_t v) {
+    return FillSeg{p, (int64_t)(bytes / 4), v, 0};
+}
+
+// Slices of one named device buffer, one per problem or list (256-byte
+// aligned), so that every problem of a call keeps its own data.
+struct Arena {
+    std::vector<size_t> off;
+    size_t total = 0;
+    size_t add(size_t bytes) {
+        const size_t o = total;
+        total += (std::max<size_t>(bytes, 1) + 255) & ~size_t(255);
+        off.push_back(o);
+        return o;
+    }
+};
 
 }  // namespace dsc

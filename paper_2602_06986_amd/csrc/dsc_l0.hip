@@ -26,7 +26,7 @@ constexpr double TAU_TIE = 1e-11;     // RSS tie tolerance relative to ||y - mea
 
 // ------------------------------------------------------------------ prep
 // One wave per row (rows 0..S-1 of F, row S = y): Z = (f - mean) / ||f - mean||.
-__global__ __launch_bounds__(256) void k_l0_prep(int n, int S, const double* __restrict__ F,
+__device__ __forceinline__ void d_l0_prep(int n, int S, const double* __restrict__ F,
                                                  int64_t ldf, const double* __restrict__ y,
                                                  int ldz, double* __restrict__ Z,
                                                  double* __restrict__ yy) {
@@ -52,8 +52,8 @@ __global__ __launch_bounds__(256) void k_l0_prep(int n, int S, const double* __r
 // G = Z Z^T for (S+1) rows: 64x64 tiles (upper triangle only, mirrored),
 // 4x4 outputs per thread, samples staged through LDS in chunks of 16 and
 // read back as double2 pairs.
-__global__ __launch_bounds__(256) void k_gram(int M, int ldz, int nk, const double* __restrict__ Z,
-                                              double* __restrict__ G, int ldg) {
+__device__ __forceinline__ void d_gram(int M, int ldz, int nk, const double* __restrict__ Z,
+                                       double* __restrict__ G, int ldg) {
     __shared__ __align__(16) double As[16][64];
     __shared__ __align__(16) double Bs[16][64];
     const int bi = blockIdx.y * 64, bj = blockIdx.x * 64;
@@ -106,10 +106,11 @@ struct SweepArgs {
     int ldg, S, D;
     const double4* E;         // D = 3: (a, b) factor table, E[b * lde + a]
     int lde;
-    const int2* items;        // D = 1, 2: (a, first b) per wave
+    const int2* items;        // D = 1, 2: (a, first b) per wave; a < 0: padding
     const int4* items3;       // D = 3: (a0, c0, b_lo, b_hi) per block
     int64_t n_items;
     double* lane_q;           // [n_items][64] (D = 1, 2) or [n_items][256] (D = 3)
+    int64_t item0;            // first merged block (D = 3) or merged block of 4 waves (D = 1, 2)
 };
 
 __device__ __forceinline__ double fast_rcp(double x) {
@@ -118,9 +119,13 @@ __device__ __forceinline__ double fast_rcp(double x) {
     return fma(r, e, r);
 }
 
+// The sweeps of every problem of a call run as one launch: block i of the
+// grid belongs to problem bprob[i]; a problem's blocks are contiguous.
 // D = 1: lane a.
-__global__ __launch_bounds__(256) void k_sweep1(SweepArgs g) {
-    const int64_t it = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+__global__ __launch_bounds__(256) void k_sweep1(ctab<SweepArgs> A, const int* __restrict__ bprob) {
+    const SweepArgs& g = tab(A, bprob[blockIdx.x]);
+    DSC_GLOBAL(g.G); DSC_GLOBAL(g.items); DSC_GLOBAL(g.lane_q);
+    const int64_t it = ((int64_t)blockIdx.x - g.item0) * 4 + (threadIdx.x >> 6);
     if (it >= g.n_items) return;
     const int lane = threadIdx.x & 63;
     const int a = g.items[it].y + lane;
@@ -144,8 +149,10 @@ __device__ __forceinline__ double q2(const double* G, int ldg, int S, int a, int
     return piv > PIV_TOL ? ca * ca / caa + e * e / piv : -1.0;
 }
 
-__global__ __launch_bounds__(256) void k_sweep2(SweepArgs g) {
-    const int64_t it = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+__global__ __launch_bounds__(256) void k_sweep2(ctab<SweepArgs> A, const int* __restrict__ bprob) {
+    const SweepArgs& g = tab(A, bprob[blockIdx.x]);
+    DSC_GLOBAL(g.G); DSC_GLOBAL(g.items); DSC_GLOBAL(g.lane_q);
+    const int64_t it = ((int64_t)blockIdx.x - g.item0) * 4 + (threadIdx.x >> 6);
     if (it >= g.n_items) return;
     const int lane = threadIdx.x & 63;
     const int a = g.items[it].x, b = g.items[it].y + lane;
@@ -199,8 +206,8 @@ __device__ __forceinline__ double sw3_q(const double4& e, const Sw3Lane& L, doub
 // Entries that cannot form a triple (b <= a, a >= S - 2, a or the pair
 // (a, b) singular) carry h_b = NaN: den is then NaN and fails the pivot
 // test for every c.
-__global__ __launch_bounds__(256) void k_sw3_table(const double* __restrict__ G, int ldg, int S,
-                                                   double4* __restrict__ E, int lde) {
+__device__ __forceinline__ void d_sw3_table(const double* __restrict__ G, int ldg, int S,
+                                            double4* __restrict__ E, int lde) {
     const int b = blockIdx.y;
     const int a = blockIdx.x * 256 + threadIdx.x;
     if (a >= lde || a > b + 15) return;
@@ -267,13 +274,16 @@ __device__ __forceinline__ void sw3_run(const double4* __restrict__ Ew, int lde,
     }
 }
 
-__global__ __launch_bounds__(256) void k_sweep3(SweepArgs g) {
-    const int4 item = g.items3[blockIdx.x];
+__global__ __launch_bounds__(256) void k_sweep3(ctab<SweepArgs> A, const int* __restrict__ bprob) {
+    const SweepArgs& g = tab(A, bprob[blockIdx.x]);
+    DSC_GLOBAL(g.G); DSC_GLOBAL(g.E); DSC_GLOBAL(g.items3); DSC_GLOBAL(g.lane_q);
+    const int64_t li = (int64_t)blockIdx.x - g.item0;   // block within its problem
+    const int4 item = g.items3[li];
     const int a0 = item.x, c0 = item.y;                  // block: a0..a0+15, c0..c0+63, b in [z, w)
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int c = c0 + lane;
-    double* out = g.lane_q + ((int64_t)blockIdx.x * 4 + wv) * (SW3_A * 64);
+    double* out = g.lane_q + (li * 4 + wv) * (SW3_A * 64);
     if (a0 < 0) {                                        // padding block (uniform)
         for (int k = 0; k < SW3_A; k++) out[k * 64 + lane] = -1.0;
         return;
@@ -343,7 +353,10 @@ __device__ __forceinline__ void band_push(const BandArgs& g, int a, int b, int c
     if ((int64_t)slot < g.bcap) g.band[slot] = make_int4(a, b, c, 0);
 }
 
-__global__ __launch_bounds__(256) void k_band_lanes(BandArgs g) {
+// grid (blocks, problems)
+__global__ __launch_bounds__(256) void k_band_lanes(ctab<BandArgs> A) {
+    const BandArgs& g = tab(A, blockIdx.y);
+    DSC_GLOBAL(g.lane_q); DSC_GLOBAL(g.items); DSC_GLOBAL(g.items3); DSC_GLOBAL(g.sel); DSC_GLOBAL(g.st); DSC_GLOBAL(g.band); DSC_GLOBAL(g.bcnt); DSC_GLOBAL(g.pairs); DSC_GLOBAL(g.pcnt);
     const double thr = band_thr(g);
     const int per = g.D == 3 ? 4 * SW3_A * 64 : 64;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < g.n_lanes;
@@ -364,7 +377,9 @@ __global__ __launch_bounds__(256) void k_band_lanes(BandArgs g) {
 }
 
 // D = 3: one wave per listed (a, c) lane; its lanes split the b range.
-__global__ __launch_bounds__(256) void k_band_expand3(BandArgs g) {
+__global__ __launch_bounds__(256) void k_band_expand3(ctab<BandArgs> A) {
+    const BandArgs& g = tab(A, blockIdx.y);
+    DSC_GLOBAL(g.G); DSC_GLOBAL(g.E); DSC_GLOBAL(g.sel); DSC_GLOBAL(g.st); DSC_GLOBAL(g.band); DSC_GLOBAL(g.bcnt); DSC_GLOBAL(g.pairs); DSC_GLOBAL(g.pcnt);
     const double thr = band_thr(g);
     const int64_t np = min((int64_t)*g.pcnt, g.pcap);
     const int lane = threadIdx.x & 63;
@@ -461,7 +476,7 @@ __device__ void block_lsq(int n, int d, const int* idx, const double* __restrict
 }
 
 // One workgroup per band entry (persistent over the band).
-__global__ __launch_bounds__(256) void k_refit(int n, int D, const double* __restrict__ F,
+__device__ __forceinline__ void d_refit(int n, int D, const double* __restrict__ F,
                                                int64_t ldf, const double* __restrict__ y,
                                                const int4* __restrict__ band,
                                                const unsigned long long* __restrict__ bcnt,
@@ -487,14 +502,14 @@ __global__ __launch_bounds__(256) void k_refit(int n, int D, const double* __res
 
 // Rank the band (one thread): repeatedly take the minimum RSS; entries
 // within TAU_TIE * yy of it are tied and the smallest sorted-ID tuple wins.
-__global__ void k_rank_models(const int4* __restrict__ band, const double* __restrict__ brss,
+__device__ __forceinline__ void d_rank_models(const int4* __restrict__ band, const double* __restrict__ brss,
                               const double* __restrict__ bcoef,
                               const unsigned long long* __restrict__ bcnt, int64_t bcap, int D, int m,
                               const int64_t* __restrict__ ids, const double* __restrict__ yyp,
                               int n, uint8_t* __restrict__ taken, int32_t* __restrict__ out_sub,
                               double* __restrict__ out_rmse, double* __restrict__ out_coef,
                               int32_t* __restrict__ chosen) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (threadIdx.x != 0) return;
     const double yy = *yyp;
     const int64_t nb = min((int64_t)*bcnt, bcap);
     for (int64_t e = 0; e < nb; e++) taken[e] = !(brss[e] >= 0.0);
@@ -542,7 +557,7 @@ __global__ void k_rank_models(const int4* __restrict__ band, const double* __res
 }
 
 // Residuals of the chosen models: one block per model.
-__global__ __launch_bounds__(256) void k_resid(int n, int D, const double* __restrict__ F,
+__device__ __forceinline__ void d_resid(int n, int D, const double* __restrict__ F,
                                                int64_t ldf, const double* __restrict__ y,
                                                const int32_t* __restrict__ sub,
                                                const double* __restrict__ coef,
@@ -559,6 +574,90 @@ __global__ __launch_bounds__(256) void k_resid(int n, int D, const double* __res
         for (int j = 0; j < D; j++) p = fma(c[j + 1], F[(int64_t)s[j] * ldf + i], p);
         out[q * ldr + i] = y[i] - p;
     }
+}
+
+// ------------------------------------------------ batched kernel entries
+struct PrepArgs {
+    int n, S, ldz, ldg;
+    const double* F;
+    int64_t ldf;
+    const double* y;
+    double *Z, *G, *yy;
+    double4* E;               // D = 3 factor table
+    int lde;
+};
+
+// grid (row blocks of 4, problems)
+__global__ __launch_bounds__(256) void k_l0_prep(ctab<PrepArgs> A) {
+    const PrepArgs& a = tab(A, blockIdx.y);
+    DSC_GLOBAL(a.F); DSC_GLOBAL(a.y); DSC_GLOBAL(a.Z); DSC_GLOBAL(a.yy);
+    if ((int)blockIdx.x * 4 > a.S) return;
+    d_l0_prep(a.n, a.S, a.F, a.ldf, a.y, a.ldz, a.Z, a.yy);
+}
+
+// One problem (used by OMP): grid (row blocks of 4).
+__global__ __launch_bounds__(256) void k_l0_prep_one(int n, int S, const double* __restrict__ F,
+                                                     int64_t ldf, const double* __restrict__ y, int ldz,
+                                                     double* __restrict__ Z, double* __restrict__ yy) {
+    d_l0_prep(n, S, F, ldf, y, ldz, Z, yy);
+}
+
+// grid (column tiles, row tiles, problems)
+__global__ __launch_bounds__(256) void k_gram(ctab<PrepArgs> A) {
+    const PrepArgs& a = tab(A, blockIdx.z);
+    DSC_GLOBAL(a.Z); DSC_GLOBAL(a.G);
+    const int M = a.S + 1;
+    if ((int)blockIdx.x * 64 >= M || (int)blockIdx.y * 64 >= M) return;
+    d_gram(M, a.ldz, a.ldz, a.Z, a.G, a.ldg);
+}
+
+// grid (a blocks, b rows, problems)
+__global__ __launch_bounds__(256) void k_sw3_table(ctab<PrepArgs> A) {
+    const PrepArgs& a = tab(A, blockIdx.z);
+    DSC_GLOBAL(a.G); DSC_GLOBAL(a.E);
+    if ((int)blockIdx.y >= a.S || (int)blockIdx.x * 256 >= a.lde) return;
+    d_sw3_table(a.G, a.ldg, a.S, a.E, a.lde);
+}
+
+struct RefitArgs {
+    int n, D, m;
+    const double* F;
+    int64_t ldf;
+    const double* y;
+    const int4* band;
+    const unsigned long long* bcnt;
+    int64_t bcap;
+    double *scratch, *brss, *bcoef;
+    const int64_t* ids;
+    const double* yy;
+    uint8_t* taken;
+    int32_t* out_sub;
+    double *out_rmse, *out_coef;
+    int32_t* chosen;
+    double* out_resid;
+    int64_t ldr;
+};
+
+// grid (persistent blocks, problems)
+__global__ __launch_bounds__(256) void k_refit(ctab<RefitArgs> A) {
+    const RefitArgs& a = tab(A, blockIdx.y);
+    DSC_GLOBAL(a.F); DSC_GLOBAL(a.y); DSC_GLOBAL(a.band); DSC_GLOBAL(a.bcnt); DSC_GLOBAL(a.scratch); DSC_GLOBAL(a.brss); DSC_GLOBAL(a.bcoef); DSC_GLOBAL(a.ids); DSC_GLOBAL(a.yy); DSC_GLOBAL(a.taken); DSC_GLOBAL(a.out_sub); DSC_GLOBAL(a.out_rmse); DSC_GLOBAL(a.out_coef); DSC_GLOBAL(a.chosen);
+    d_refit(a.n, a.D, a.F, a.ldf, a.y, a.band, a.bcnt, a.bcap, a.scratch, a.brss, a.bcoef);
+}
+
+// grid (problems), 64 threads
+__global__ void k_rank_models(ctab<RefitArgs> A) {
+    const RefitArgs& a = tab(A, blockIdx.x);
+    DSC_GLOBAL(a.F); DSC_GLOBAL(a.y); DSC_GLOBAL(a.band); DSC_GLOBAL(a.bcnt); DSC_GLOBAL(a.scratch); DSC_GLOBAL(a.brss); DSC_GLOBAL(a.bcoef); DSC_GLOBAL(a.ids); DSC_GLOBAL(a.yy); DSC_GLOBAL(a.taken); DSC_GLOBAL(a.out_sub); DSC_GLOBAL(a.out_rmse); DSC_GLOBAL(a.out_coef); DSC_GLOBAL(a.chosen);
+    d_rank_models(a.band, a.brss, a.bcoef, a.bcnt, a.bcap, a.D, a.m, a.ids, a.yy, a.n, a.taken,
+                  a.out_sub, a.out_rmse, a.out_coef, a.chosen);
+}
+
+// grid (models, problems)
+__global__ __launch_bounds__(256) void k_resid(ctab<RefitArgs> A) {
+    const RefitArgs& a = tab(A, blockIdx.y);
+    DSC_GLOBAL(a.F); DSC_GLOBAL(a.y); DSC_GLOBAL(a.out_sub); DSC_GLOBAL(a.out_coef); DSC_GLOBAL(a.out_resid);
+    d_resid(a.n, a.D, a.F, a.ldf, a.y, a.out_sub, a.out_coef, a.out_resid, a.ldr);
 }
 
 // ------------------------------------------------------------------ OMP
@@ -652,29 +751,18 @@ __global__ __launch_bounds__(256) void k_row_norm(int S, int ldz, const double* 
     if (lane == 0) nrm[j] = s;
 }
 
-// ================================================================== host
-struct L0Plan {
-    int S, n, ldz, ldg;
-    double *Z, *G, *yy;
-};
-
-static void prep_gram(discover_ctx* ctx, const discover_l0_problem& pb, L0Plan& L, hipStream_t st) {
-    L.S = pb.S;
-    L.n = pb.n;
-    L.ldz = (int)cdiv(pb.n, 16) * 16;
-    L.ldg = (int)cdiv(pb.S + 1, 2) * 2;
-    L.Z = ctx->buf<double>("l0Z", (size_t)(pb.S + 1) * L.ldz);
-    L.G = ctx->buf<double>("l0G", (size_t)(pb.S + 1) * L.ldg);
-    L.yy = ctx->buf<double>("l0yy", 1);
-    KTimer kt(ctx, st, "l0_gram");
-    k_l0_prep<<<(unsigned)cdiv(pb.S + 1, 4), 256, 0, st>>>(pb.n, pb.S, pb.F, pb.ldf, pb.y, L.ldz, L.Z,
-                                                           L.yy);
-    const int M = pb.S + 1;
-    dim3 g((unsigned)cdiv(M, 64), (unsigned)cdiv(M, 64));
-    k_gram<<<g, 256, 0, st>>>(M, L.ldz, L.ldz, L.Z, L.G, L.ldg);
-    check_launch("k_gram");
+// OMP set-up and result, as kernels so that no host copy is needed.
+__global__ void k_omp_init(int32_t* __restrict__ active, int D_max, const int32_t* __restrict__ init,
+                           int n_init, int32_t* __restrict__ nact) {
+    for (int q = threadIdx.x; q < D_max; q += blockDim.x) active[q] = q < n_init ? init[q] : -1;
+    if (threadIdx.x == 0) *nact = n_init;
 }
 
+__global__ void k_omp_rmse(const double* __restrict__ rss, int n, double* __restrict__ out) {
+    if (threadIdx.x == 0) *out = sqrt(*rss / n);
+}
+
+// ================================================================== host
 // D = 3 blocks (16 consecutive a, 64 consecutive c).  Column groups of 64
 // are dealt to the 8 XCDs by longest-processing-time on their total work,
 // and block p of the grid runs on XCD p mod 8, so each XCD's L2 holds only
@@ -722,104 +810,243 @@ static std::vector<int4> sweep3_blocks(int S) {
     return out;
 }
 
-static void l0_problem(discover_ctx* ctx, const discover_l0_problem& pb, int D, int m,
-                       int32_t* out_sub, double* out_rmse, double* out_coef, double* out_resid,
-                       int64_t ldr, discover_l0_stats& stats, hipStream_t st) {
-    L0Plan L;
-    prep_gram(ctx, pb, L, st);
-    const int S = pb.S;
-    std::vector<int2> items;
-    std::vector<int4> items3;
-    int per = 64;
+// Sweep work items of one subspace size (cached: they depend on S and D only).
+struct L0Items {
+    std::vector<int2> items;      // D = 1, 2
+    std::vector<int4> items3;     // D = 3
+};
+
+static std::shared_ptr<L0Items> l0_items(discover_ctx* ctx, int S, int D) {
+    const std::string key = "l0items:" + std::to_string(S) + ":" + std::to_string(D);
+    auto it = ctx->plans.find(key);
+    if (it != ctx->plans.end()) return std::static_pointer_cast<L0Items>(it->second);
+    auto P = std::make_shared<L0Items>();
     if (D == 1) {
-        for (int a0 = 0; a0 < S; a0 += 64) items.push_back(make_int2(0, a0));
+        for (int a0 = 0; a0 < S; a0 += 64) P->items.push_back(make_int2(0, a0));
     } else if (D == 2) {
         for (int a = 0; a < S - 1; a++)
-            for (int b0 = a + 1; b0 < S; b0 += 64) items.push_back(make_int2(a, b0));
+            for (int b0 = a + 1; b0 < S; b0 += 64) P->items.push_back(make_int2(a, b0));
     } else {
-        items3 = sweep3_blocks(S);
-        per = 4 * SW3_A * 64;
+        P->items3 = sweep3_blocks(S);
     }
-    const int64_t ni = D == 3 ? (int64_t)items3.size() : (int64_t)items.size();
-    const int64_t nl = ni * per;
-    int2* d_items = ctx->buf<int2>("l0items", D == 3 ? 1 : ni);
-    int4* d_items3 = ctx->buf<int4>("l0items3", D == 3 ? ni : 1);
-    if (D == 3)
-        DSC_HIP(hipMemcpyAsync(d_items3, items3.data(), ni * sizeof(int4), hipMemcpyHostToDevice, st));
-    else
-        DSC_HIP(hipMemcpyAsync(d_items, items.data(), ni * sizeof(int2), hipMemcpyHostToDevice, st));
-    SweepArgs g{};
-    g.G = L.G; g.ldg = L.ldg; g.S = S; g.D = D; g.items = d_items; g.items3 = d_items3; g.n_items = ni;
-    g.lane_q = ctx->buf<double>("l0laneq", nl);
+    if (ctx->plans.size() >= 64) ctx->plans.clear();
+    ctx->plans[key] = P;
+    return P;
+}
+
+struct BandMemo {
+    std::vector<int64_t> cap;
+};
+
+// Exhaustive L0 of every problem of a call, one launch per phase.
+static void l0_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D, int m,
+                     int32_t* out_sub, double* out_rmse, double* out_coef, double* out_resid,
+                     int64_t ldr, std::vector<discover_l0_stats>& stats, hipStream_t st) {
+    // 1. layout
+    std::vector<std::shared_ptr<L0Items>> its(nb);
+    std::vector<PrepArgs> pa(nb);
+    std::vector<int64_t> ni(nb), nblk(nb), lane0(nb), blk0(nb);
+    const int per = D == 3 ? 4 * SW3_A * 64 : 64;
+    Arena ar;
+    std::vector<std::vector<size_t>> o(nb);
+    int64_t tot_blk = 0, tot_items = 0, tot_items3 = 0, tot_lanes = 0;
+    int Smax = 0, ldemax = 0;
+    for (int b = 0; b < nb; b++) {
+        const discover_l0_problem& pb = probs[b];
+        its[b] = l0_items(ctx, pb.S, D);
+        ni[b] = D == 3 ? (int64_t)its[b]->items3.size() : (int64_t)its[b]->items.size();
+        nblk[b] = D == 3 ? ni[b] : cdiv(ni[b], 4);
+        blk0[b] = tot_blk;
+        tot_blk += nblk[b];
+        lane0[b] = tot_lanes;
+        tot_lanes += ni[b] * per;
+        PrepArgs& a = pa[b];
+        a = PrepArgs{};
+        a.n = pb.n; a.S = pb.S; a.ldz = (int)cdiv(pb.n, 16) * 16; a.ldg = (int)cdiv(pb.S + 1, 2) * 2;
+        a.F = pb.F; a.ldf = pb.ldf; a.y = pb.y;
+        a.lde = D == 3 ? (int)cdiv(pb.S + 16, 4) * 4 : 0;
+        auto& v = o[b];
+        v.push_back(ar.add((size_t)(pb.S + 1) * a.ldz * 8));               // Z
+        v.push_back(ar.add((size_t)(pb.S + 1) * a.ldg * 8));               // G
+        v.push_back(ar.add(8));                                            // yy
+        v.push_back(ar.add(D == 3 ? (size_t)pb.S * a.lde * 32 : 32));      // E
+        Smax = std::max(Smax, pb.S);
+        ldemax = std::max(ldemax, a.lde);
+        if (D == 3) tot_items3 += ni[b]; else tot_items += ni[b];
+    }
+    char* base = (char*)ctx->raw("l0_arena", ar.total);
+    for (int b = 0; b < nb; b++) {
+        pa[b].Z = (double*)(base + o[b][0]);
+        pa[b].G = (double*)(base + o[b][1]);
+        pa[b].yy = (double*)(base + o[b][2]);
+        pa[b].E = (double4*)(base + o[b][3]);
+    }
+    const ctab<PrepArgs> dpa = ct(ctx->upload("l0_prep", pa, st));
+    // 2. Gram matrices (and the D = 3 factor tables)
+    {
+        KTimer kt(ctx, st, "l0_gram");
+        k_l0_prep<<<dim3((unsigned)cdiv(Smax + 1, 4), nb), 256, 0, st>>>(dpa);
+        const unsigned gt = (unsigned)cdiv(Smax + 1, 64);
+        k_gram<<<dim3(gt, gt, nb), 256, 0, st>>>(dpa);
+        check_launch("k_gram");
+    }
     if (D == 3) {
-        g.lde = (int)cdiv(S + 16, 4) * 4;
-        double4* E = ctx->buf<double4>("l0sw3tab", (size_t)S * g.lde);
-        g.E = E;
         KTimer kt(ctx, st, "l0_table");
-        dim3 gt((unsigned)cdiv(g.lde, 256), (unsigned)S);
-        k_sw3_table<<<gt, 256, 0, st>>>(L.G, L.ldg, S, E, g.lde);
+        k_sw3_table<<<dim3((unsigned)cdiv(ldemax, 256), (unsigned)Smax, nb), 256, 0, st>>>(dpa);
         check_launch("k_sw3_table");
     }
+    // 3. sweep over the merged work items
+    std::vector<int2> items;
+    std::vector<int4> items3;
+    std::vector<int> bprob;
+    std::vector<int64_t> item_off(nb);
+    for (int b = 0; b < nb; b++) {
+        item_off[b] = D == 3 ? (int64_t)items3.size() : (int64_t)items.size();
+        if (D == 3) items3.insert(items3.end(), its[b]->items3.begin(), its[b]->items3.end());
+        else items.insert(items.end(), its[b]->items.begin(), its[b]->items.end());
+        bprob.insert(bprob.end(), (size_t)nblk[b], b);
+    }
+    const int2* d_items = D == 3 ? nullptr : ctx->upload("l0_items", items, st);
+    const int4* d_items3 = D == 3 ? ctx->upload("l0_items3", items3, st) : nullptr;
+    const int* d_bprob = ctx->upload("l0_bprob", bprob, st);
+    double* lane_q = ctx->buf<double>("l0_laneq", (size_t)tot_lanes);
+    std::vector<SweepArgs> sa(nb);
+    for (int b = 0; b < nb; b++) {
+        SweepArgs& g = sa[b];
+        g = SweepArgs{};
+        g.G = pa[b].G; g.ldg = pa[b].ldg; g.S = probs[b].S; g.D = D; g.E = pa[b].E; g.lde = pa[b].lde;
+        g.items = d_items ? d_items + item_off[b] : nullptr;
+        g.items3 = d_items3 ? d_items3 + item_off[b] : nullptr;
+        g.n_items = ni[b];
+        g.lane_q = lane_q + lane0[b];
+        g.item0 = blk0[b];
+    }
+    const ctab<SweepArgs> dsa = ct(ctx->upload("l0_sweep", sa, st));
     {
         KTimer kt(ctx, st, D == 3 ? "l0_sweep3" : "l0_sweep");
-        if (D == 1) k_sweep1<<<(unsigned)cdiv(ni, 4), 256, 0, st>>>(g);
-        else if (D == 2) k_sweep2<<<(unsigned)cdiv(ni, 4), 256, 0, st>>>(g);
-        else k_sweep3<<<(unsigned)ni, 256, 0, st>>>(g);
+        if (tot_blk) {
+            if (D == 1) k_sweep1<<<(unsigned)tot_blk, 256, 0, st>>>(dsa, d_bprob);
+            else if (D == 2) k_sweep2<<<(unsigned)tot_blk, 256, 0, st>>>(dsa, d_bprob);
+            else k_sweep3<<<(unsigned)tot_blk, 256, 0, st>>>(dsa, d_bprob);
+        }
         check_launch("k_sweep");
     }
-    uint32_t* hist = ctx->buf<uint32_t>("l0hist", 4096);
-    uint32_t* sel = ctx->buf<uint32_t>("l0sel", 4);
-    int64_t* sst = ctx->buf<int64_t>("l0selst", 2);
-    BandArgs bg{};
-    bg.G = L.G; bg.ldg = L.ldg; bg.S = S; bg.D = D; bg.items = d_items; bg.items3 = d_items3;
-    bg.E = g.E; bg.lde = g.lde;
-    bg.n_lanes = nl;
-    bg.lane_q = g.lane_q; bg.sel = sel; bg.st = sst;
-    bg.bcnt = ctx->buf<unsigned long long>("l0bcnt", 2);
-    bg.pcnt = bg.bcnt + 1;
-    int64_t cap = std::max<int64_t>(1 << 16, 256 * (int64_t)m);
-    for (;;) {
-        bg.bcap = cap;
-        bg.pcap = cap;
-        bg.band = ctx->buf<int4>("l0band", cap);
-        bg.pairs = ctx->buf<int4>("l0pairs", cap);
-        DSC_HIP(hipMemsetAsync(bg.bcnt, 0, 16, st));
+    // 4. band: radix selection of the m-th best lane, expansion, QR refit, ranking
+    std::vector<int64_t> cap(nb, std::max<int64_t>(1 << 16, 256 * (int64_t)m));
+    std::string ck((const char*)&D, sizeof D);
+    ck.append((const char*)&m, sizeof m);
+    for (int b = 0; b < nb; b++) {
+        const int64_t f[5] = {probs[b].n, probs[b].S, (int64_t)(intptr_t)probs[b].F,
+                              (int64_t)(intptr_t)probs[b].y, (int64_t)(intptr_t)probs[b].ids};
+        ck.append((const char*)f, sizeof f);
+    }
+    auto mit = ctx->batches.find("band" + ck);
+    if (mit != ctx->batches.end()) {
+        const BandMemo& bm = *std::static_pointer_cast<BandMemo>(mit->second);
+        if ((int)bm.cap.size() == nb) cap = bm.cap;
+    }
+    std::vector<int> act(nb);
+    for (int b = 0; b < nb; b++) act[b] = b;
+    const int nblk_refit = std::max(8, std::min(512, 4096 / nb));
+    while (!act.empty()) {
+        const int na = (int)act.size();
+        Arena br;
+        std::vector<std::vector<size_t>> bo(na);
+        for (int q = 0; q < na; q++) {
+            const int b = act[q];
+            const size_t c = (size_t)cap[b];
+            auto& v = bo[q];
+            v.push_back(br.add(c * 16));                                   // band
+            v.push_back(br.add(c * 16));                                   // pairs
+            v.push_back(br.add(c * 8));                                    // brss
+            v.push_back(br.add(c * (D + 1) * 8));                          // bcoef
+            v.push_back(br.add(c));                                        // taken
+            v.push_back(br.add((size_t)m * 4));                            // chosen
+            v.push_back(br.add((size_t)nblk_refit * (D + 2) * probs[b].n * 8));  // refit scratch
+            v.push_back(br.add(64));                                       // bcnt, pcnt, st[2], sel[4]
+            v.push_back(br.add(4096 * 4));                                 // hist
+        }
+        char* bb = (char*)ctx->raw("l0_band_arena", br.total);
+        std::vector<BandArgs> ba(na);
+        std::vector<RadixArgs> ra(na);
+        std::vector<RefitArgs> fa(na);
+        std::vector<FillSeg> fills;
+        int64_t lanes_max = 1;
+        for (int q = 0; q < na; q++) {
+            const int b = act[q];
+            const auto& v = bo[q];
+            char* misc = bb + v[7];
+            BandArgs& g = ba[q];
+            g = BandArgs{};
+            g.G = pa[b].G; g.ldg = pa[b].ldg; g.S = probs[b].S; g.D = D; g.E = pa[b].E; g.lde = pa[b].lde;
+            g.items = sa[b].items; g.items3 = sa[b].items3;
+            g.n_lanes = ni[b] * per;
+            g.lane_q = sa[b].lane_q;
+            g.sel = (uint32_t*)(misc + 32); g.st = (int64_t*)(misc + 16);
+            g.band = (int4*)(bb + v[0]); g.bcnt = (unsigned long long*)misc; g.bcap = cap[b];
+            g.pairs = (int4*)(bb + v[1]); g.pcnt = (unsigned long long*)misc + 1; g.pcap = cap[b];
+            ra[q] = RadixArgs{g.lane_q, g.n_lanes, m, (uint32_t*)(bb + v[8]), (uint32_t*)(misc + 32),
+                              (int64_t*)(misc + 16)};
+            fills.push_back(fill_seg(misc, 16, 0u));
+            lanes_max = std::max(lanes_max, g.n_lanes);
+            RefitArgs& f = fa[q];
+            f = RefitArgs{};
+            f.n = probs[b].n; f.D = D; f.m = m; f.F = probs[b].F; f.ldf = probs[b].ldf; f.y = probs[b].y;
+            f.band = g.band; f.bcnt = g.bcnt; f.bcap = cap[b];
+            f.scratch = (double*)(bb + v[6]); f.brss = (double*)(bb + v[2]); f.bcoef = (double*)(bb + v[3]);
+            f.ids = probs[b].ids; f.yy = pa[b].yy; f.taken = (uint8_t*)(bb + v[4]);
+            f.out_sub = out_sub + (int64_t)b * m * D; f.out_rmse = out_rmse + (int64_t)b * m;
+            f.out_coef = out_coef + (int64_t)b * m * (D + 1); f.chosen = (int32_t*)(bb + v[5]);
+            f.out_resid = out_resid ? out_resid + (int64_t)b * m * ldr : nullptr;
+            f.ldr = ldr;
+        }
+        fill_all(ctx, "l0_fills", fills, st);
+        const ctab<BandArgs> dba = ct(ctx->upload("l0_band", ba, st));
+        const RadixArgs* dra = ctx->upload("l0_radix", ra, st);
+        const ctab<RefitArgs> dfa = ct(ctx->upload("l0_refit", fa, st));
         {
             KTimer kt(ctx, st, "l0_band");
-            radix_select(g.lane_q, nl, m, hist, sel, sst, st);
-            k_band_lanes<<<(unsigned)std::min<int64_t>(1024, cdiv(nl, 256)), 256, 0, st>>>(bg);
-            if (D == 3) k_band_expand3<<<1024, 256, 0, st>>>(bg);
+            radix_select(dra, na, lanes_max, st);
+            const unsigned lb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(std::max(8, 1024 / na),
+                                                                                cdiv(lanes_max, 256)));
+            k_band_lanes<<<dim3(lb, na), 256, 0, st>>>(dba);
+            if (D == 3) k_band_expand3<<<dim3((unsigned)std::max(8, 1024 / na), na), 256, 0, st>>>(dba);
             check_launch("k_band");
         }
-        // refit every band subset by QR (persistent blocks over the device count)
-        const int nblk = 512;
-        double* scratch = ctx->buf<double>("l0scratch", (size_t)nblk * (D + 2) * pb.n);
-        double* brss = ctx->buf<double>("l0brss", cap);
-        double* bcoef = ctx->buf<double>("l0bcoef", cap * (D + 1));
         {
             KTimer kt(ctx, st, "l0_refit");
-            k_refit<<<nblk, 256, 0, st>>>(pb.n, D, pb.F, pb.ldf, pb.y, bg.band, bg.bcnt, cap, scratch,
-                                          brss, bcoef);
+            k_refit<<<dim3(nblk_refit, na), 256, 0, st>>>(dfa);
             check_launch("k_refit");
         }
-        uint8_t* taken = ctx->buf<uint8_t>("l0taken", cap);
-        int32_t* chosen = ctx->buf<int32_t>("l0chosen", m);
-        k_rank_models<<<1, 64, 0, st>>>(bg.band, brss, bcoef, bg.bcnt, cap, D, m, pb.ids, L.yy, pb.n,
-                                        taken, out_sub, out_rmse, out_coef, chosen);
+        k_rank_models<<<na, 64, 0, st>>>(dfa);
         check_launch("k_rank_models");
-        unsigned long long cnt[2];
-        DSC_HIP(hipMemcpyAsync(cnt, bg.bcnt, 16, hipMemcpyDeviceToHost, st));
-        DSC_HIP(hipStreamSynchronize(st));
-        if ((int64_t)cnt[0] <= cap && (int64_t)cnt[1] <= cap) {
-            stats.n_band = (int64_t)cnt[0];
-            if (cnt[0] == 0) DSC_FAIL(DISCOVER_E_NUMERIC, "no non-singular %d-subset", D);
-            break;
+        if (out_resid) {
+            k_resid<<<dim3(m, na), 256, 0, st>>>(dfa);
+            check_launch("k_resid");
         }
-        cap = (int64_t)std::max(cnt[0], cnt[1]) + 1024;
+        if (ctx->capturing) break;              // capacities are checked after the replay
+        std::vector<unsigned long long> cnt(2 * (size_t)na);
+        for (int q = 0; q < na; q++)
+            DSC_HIP(hipMemcpyAsync(&cnt[2 * q], ba[q].bcnt, 16, hipMemcpyDeviceToHost, st));
+        DSC_HIP(hipStreamSynchronize(st));
+        std::vector<int> next;
+        for (int q = 0; q < na; q++) {
+            const int b = act[q];
+            if ((int64_t)cnt[2 * q] <= cap[b] && (int64_t)cnt[2 * q + 1] <= cap[b]) {
+                stats[b].n_band = (int64_t)cnt[2 * q];
+                if (cnt[2 * q] == 0) DSC_FAIL(DISCOVER_E_NUMERIC, "problem %d: no non-singular %d-subset", b, D);
+                continue;
+            }
+            cap[b] = (int64_t)std::max(cnt[2 * q], cnt[2 * q + 1]) + 1024;
+            next.push_back(b);
+        }
+        act.swap(next);
     }
-    if (out_resid) {
-        k_resid<<<m, 256, 0, st>>>(pb.n, D, pb.F, pb.ldf, pb.y, out_sub, out_coef, out_resid, ldr);
-        check_launch("k_resid");
+    if (!ctx->capturing) {
+        auto bm = std::make_shared<BandMemo>();
+        bm->cap = cap;
+        if (ctx->batches.size() >= 256) ctx->batches.clear();
+        ctx->batches["band" + ck] = bm;
     }
 }
 
@@ -840,6 +1067,7 @@ extern "C" discover_status discover_l0_fit(discover_ctx* ctx, const discover_l0_
     using namespace dsc;
     return guarded([&] {
         DSC_REQUIRE(ctx && probs && n_problems >= 1, "ctx/probs");
+        DSC_REQUIRE(n_problems <= 65535, "n_problems = %d > 65535", n_problems);
         DSC_REQUIRE(D >= 1 && D <= 3, "D = %d outside 1..3", D);
         DSC_REQUIRE(m >= 1 && m <= 64, "m = %d outside 1..64", m);
         DSC_REQUIRE(out_subsets && out_rmse && out_coef, "outputs required");
@@ -852,15 +1080,17 @@ extern "C" discover_status discover_l0_fit(discover_ctx* ctx, const discover_l0_
         }
         DSC_HIP(hipSetDevice(ctx->device));
         hipStream_t st = (hipStream_t)stream;
+        std::vector<discover_l0_stats> stats(n_problems);
         for (int b = 0; b < n_problems; b++) {
-            discover_l0_stats s{};
-            s.n_subsets = binom(probs[b].S, D);
-            l0_problem(ctx, probs[b], D, m, out_subsets + (int64_t)b * m * D, out_rmse + (int64_t)b * m,
-                       out_coef + (int64_t)b * m * (D + 1),
-                       out_resid ? out_resid + (int64_t)b * m * ldr : nullptr, ldr, s, st);
+            stats[b] = discover_l0_stats{};
+            stats[b].n_subsets = binom(probs[b].S, D);
+        }
+        l0_batch(ctx, probs, n_problems, D, m, out_subsets, out_rmse, out_coef, out_resid, ldr, stats, st);
+        if (!ctx->capturing) {
             DSC_HIP(hipStreamSynchronize(st));
             ctx->resolve_timing();
-            if (out_stats) out_stats[b] = s;
+            if (out_stats)
+                for (int b = 0; b < n_problems; b++) out_stats[b] = stats[b];
         }
     });
 }
@@ -888,44 +1118,37 @@ extern "C" discover_status discover_omp(discover_ctx* ctx, const discover_l0_pro
         hipStream_t st = (hipStream_t)stream;
         for (int b = 0; b < n_problems; b++) {
             const discover_l0_problem& pb = probs[b];
-            L0Plan L;
-            L.S = pb.S;
-            L.n = pb.n;
-            L.ldz = (int)cdiv(pb.n, 16) * 16;
-            L.Z = ctx->buf<double>("ompZ", (size_t)(pb.S + 1) * L.ldz);
-            L.yy = ctx->buf<double>("ompyy", 1);
+            const std::string sfx = std::to_string(b);
+            const int ldz = (int)cdiv(pb.n, 16) * 16;
+            double* Z = ctx->buf<double>("ompZ" + sfx, (size_t)(pb.S + 1) * ldz);
+            double* yy = ctx->buf<double>("ompyy" + sfx, 1);
             int32_t* active = out_active + (int64_t)b * D_max;
-            int32_t* nact = ctx->buf<int32_t>("ompn", 1);
-            double* g = ctx->buf<double>("ompg", pb.S);
-            double* nrm = ctx->buf<double>("ompnrm", pb.S);
-            double* r = out_resid ? out_resid + (int64_t)b * ldr : ctx->buf<double>("ompr", pb.n);
-            double* A = ctx->buf<double>("ompA", (size_t)(D_max + 2) * pb.n);
-            double* rss = ctx->buf<double>("omprss", 1);
+            int32_t* nact = ctx->buf<int32_t>("ompn" + sfx, 1);
+            double* g = ctx->buf<double>("ompg" + sfx, pb.S);
+            double* nrm = ctx->buf<double>("ompnrm" + sfx, pb.S);
+            double* r = out_resid ? out_resid + (int64_t)b * ldr : ctx->buf<double>("ompr" + sfx, pb.n);
+            double* A = ctx->buf<double>("ompA" + sfx, (size_t)(D_max + 2) * pb.n);
+            double* rss = ctx->buf<double>("omprss" + sfx, 1);
             double* coef = out_coef + (int64_t)b * (D_max + 1);
             KTimer kt(ctx, st, "omp");
-            k_l0_prep<<<(unsigned)cdiv(pb.S + 1, 4), 256, 0, st>>>(pb.n, pb.S, pb.F, pb.ldf, pb.y,
-                                                                   L.ldz, L.Z, L.yy);
-            k_row_norm<<<(unsigned)cdiv(pb.S, 4), 256, 0, st>>>(pb.S, L.ldz, L.Z, pb.n, nrm);
-            DSC_HIP(hipMemsetAsync(active, 0xFF, (size_t)D_max * 4, st));
-            if (n_init)
-                DSC_HIP(hipMemcpyAsync(active, init_active + (int64_t)b * n_init, (size_t)n_init * 4,
-                                       hipMemcpyDeviceToDevice, st));
-            DSC_HIP(hipMemcpyAsync(nact, &n_init, 4, hipMemcpyHostToDevice, st));
+            k_l0_prep_one<<<(unsigned)cdiv(pb.S + 1, 4), 256, 0, st>>>(pb.n, pb.S, pb.F, pb.ldf, pb.y,
+                                                                       ldz, Z, yy);
+            k_row_norm<<<(unsigned)cdiv(pb.S, 4), 256, 0, st>>>(pb.S, ldz, Z, pb.n, nrm);
+            k_omp_init<<<1, 64, 0, st>>>(active, D_max, n_init ? init_active + (int64_t)b * n_init : nullptr,
+                                         n_init, nact);
             k_omp_fit<<<1, 256, 0, st>>>(pb.n, pb.F, pb.ldf, pb.y, active, nact, A, coef, rss, r);
             for (int step = n_init; step < D_max; step++) {
-                k_omp_corr<<<(unsigned)cdiv(pb.S, 4), 256, 0, st>>>(pb.n, pb.S, L.Z, L.ldz, r, active,
+                k_omp_corr<<<(unsigned)cdiv(pb.S, 4), 256, 0, st>>>(pb.n, pb.S, Z, ldz, r, active,
                                                                     nact, g);
                 k_omp_pick<<<1, 256, 0, st>>>(pb.S, g, pb.ids, nrm, active, nact);
                 k_omp_fit<<<1, 256, 0, st>>>(pb.n, pb.F, pb.ldf, pb.y, active, nact, A, coef, rss, r);
             }
+            k_omp_rmse<<<1, 64, 0, st>>>(rss, pb.n, out_rmse + b);
             check_launch("omp");
-            double h_rss;
-            DSC_HIP(hipMemcpyAsync(&h_rss, rss, 8, hipMemcpyDeviceToHost, st));
-            DSC_HIP(hipStreamSynchronize(st));
-            const double rm = std::sqrt(h_rss / pb.n);
-            DSC_HIP(hipMemcpyAsync(out_rmse + b, &rm, 8, hipMemcpyHostToDevice, st));
-            DSC_HIP(hipStreamSynchronize(st));
         }
-        ctx->resolve_timing();
+        if (!ctx->capturing) {
+            DSC_HIP(hipStreamSynchronize(st));
+            ctx->resolve_timing();
+        }
     });
 }

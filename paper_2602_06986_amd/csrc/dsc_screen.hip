@@ -36,10 +36,10 @@ constexpr double EPS64 = 1.1102230246251565e-16;
 
 // ------------------------------------------------------------------ targets
 // One block per target: two-pass mean, centered and unit-norm copies.
-__global__ __launch_bounds__(256) void k_targets(int n, int T, const double* __restrict__ Y,
-                                                 int64_t ldy, int ldn, double* __restrict__ Yc,
-                                                 double* __restrict__ Yn, double* __restrict__ syy,
-                                                 double* __restrict__ ysum, int* __restrict__ bad) {
+__device__ __forceinline__ void d_targets(int n, int T, const double* __restrict__ Y,
+                                          int64_t ldy, int ldn, double* __restrict__ Yc,
+                                          double* __restrict__ Yn, double* __restrict__ syy,
+                                          double* __restrict__ ysum, int* __restrict__ bad) {
     const int t = blockIdx.x;
     __shared__ double red[4];
     const double* y = Y + (int64_t)t * ldy;
@@ -77,6 +77,22 @@ __global__ __launch_bounds__(256) void k_targets(int n, int T, const double* __r
     }
 }
 
+struct TgtArgs {
+    int n, T, ldn;
+    const double* Y;
+    int64_t ldy;
+    double *Yc, *Yn, *syy, *ysum;
+    int* bad;
+};
+
+// grid (targets, problems)
+__global__ __launch_bounds__(256) void k_targets(ctab<TgtArgs> A) {
+    const TgtArgs& a = tab(A, blockIdx.y);
+    DSC_GLOBAL(a.Y); DSC_GLOBAL(a.Yc); DSC_GLOBAL(a.Yn); DSC_GLOBAL(a.syy); DSC_GLOBAL(a.ysum); DSC_GLOBAL(a.bad);
+    if ((int)blockIdx.x >= a.T) return;
+    d_targets(a.n, a.T, a.Y, a.ldy, a.ldn, a.Yc, a.Yn, a.syy, a.ysum, a.bad);
+}
+
 // ---------------------------------------------------------- materialisation
 __device__ __forceinline__ double apply_op(int op, double a, double b) {
     switch (op) {
@@ -94,7 +110,7 @@ __device__ __forceinline__ double apply_op(int op, double a, double b) {
 }
 
 // Values of the operand features of one rung: c in [c0, c1).
-__global__ void k_mat_values(int n, int ldn, int c0, int c1, const double* __restrict__ X,
+__device__ __forceinline__ void d_mat_values(int n, int ldn, int c0, int c1, const double* __restrict__ X,
                              int64_t ldx, const int8_t* __restrict__ op,
                              const int32_t* __restrict__ ca, const int32_t* __restrict__ cb,
                              const int64_t* __restrict__ raw, double* __restrict__ Vf) {
@@ -115,7 +131,7 @@ __global__ void k_mat_values(int n, int ldn, int c0, int c1, const double* __res
 
 // One wave per operand feature of one rung: validity, mean, reciprocals,
 // centered values.
-__global__ __launch_bounds__(256) void k_mat_stats(int n, int ldn, int c0, int c1,
+__device__ __forceinline__ void d_mat_stats(int n, int ldn, int c0, int c1,
                                                    const int8_t* __restrict__ mop,
                                                    const int32_t* __restrict__ ca,
                                                    const int32_t* __restrict__ cb,
@@ -175,9 +191,39 @@ __global__ __launch_bounds__(256) void k_mat_stats(int n, int ldn, int c0, int c
     }
 }
 
+// Operand features of a problem, materialised rung by rung (level = rung).
+struct MatArgs {
+    int n, ldn, nlev;
+    int rs[4];                // compact start of each materialised rung, + end
+    const double* X;
+    int64_t ldx;
+    const int8_t* op;
+    const int32_t *ca, *cb;
+    const int64_t* raw;
+    double *Vf, *Rf, *Cf, *mu, *mur, *msq;
+    uint8_t* valid;
+};
+
+// grid (sample blocks, features of the level, problems)
+__global__ void k_mat_values(ctab<MatArgs> A, int level) {
+    const MatArgs& a = tab(A, blockIdx.z);
+    DSC_GLOBAL(a.X); DSC_GLOBAL(a.op); DSC_GLOBAL(a.ca); DSC_GLOBAL(a.cb); DSC_GLOBAL(a.raw); DSC_GLOBAL(a.Vf);
+    if (level >= a.nlev) return;
+    d_mat_values(a.n, a.ldn, a.rs[level], a.rs[level + 1], a.X, a.ldx, a.op, a.ca, a.cb, a.raw, a.Vf);
+}
+
+// grid (feature blocks of 4, problems)
+__global__ __launch_bounds__(256) void k_mat_stats(ctab<MatArgs> A, int level) {
+    const MatArgs& a = tab(A, blockIdx.y);
+    DSC_GLOBAL(a.op); DSC_GLOBAL(a.ca); DSC_GLOBAL(a.cb); DSC_GLOBAL(a.Vf); DSC_GLOBAL(a.Rf); DSC_GLOBAL(a.Cf); DSC_GLOBAL(a.mu); DSC_GLOBAL(a.mur); DSC_GLOBAL(a.msq); DSC_GLOBAL(a.valid);
+    if (level >= a.nlev) return;
+    d_mat_stats(a.n, a.ldn, a.rs[level], a.rs[level + 1], a.op, a.ca, a.cb, a.Vf, a.Rf, a.Cf, a.mu,
+                a.mur, a.msq, a.valid);
+}
+
 // Feature-major [M][ldn] -> sample-major [n][ldm] (padding left as is).
-__global__ void k_transpose(int n, int M, int ldn, int ldm, const double* __restrict__ src,
-                            double* __restrict__ dst) {
+__device__ __forceinline__ void d_transpose(int n, int M, int ldn, int ldm, const double* __restrict__ src,
+                                            double* __restrict__ dst) {
     __shared__ double tile[32][33];
     const int c0 = blockIdx.y * 32, s0 = blockIdx.x * 32;
     for (int k = threadIdx.y; k < 32; k += 8) {
@@ -189,6 +235,21 @@ __global__ void k_transpose(int n, int M, int ldn, int ldm, const double* __rest
         const int s = s0 + k, c = c0 + threadIdx.x;
         if (s < n && c < M) dst[(int64_t)s * ldm + c] = tile[threadIdx.x][k];
     }
+}
+
+struct TrArgs {
+    int n, M, ldn, ldm;
+    const double* src[3];
+    double* dst[3];
+};
+
+// grid (sample tiles, feature tiles, 3 x problems)
+__global__ void k_transpose(ctab<TrArgs> A) {
+    const TrArgs& a = tab(A, blockIdx.z / 3);
+    const int w = blockIdx.z % 3;
+    DSC_GLOBAL(a.src[w]); DSC_GLOBAL(a.dst[w]);
+    if ((int)blockIdx.x * 32 >= a.n || (int)blockIdx.y * 32 >= a.M) return;
+    d_transpose(a.n, a.M, a.ldn, a.ldm, a.src[w], a.dst[w]);
 }
 
 // ----------------------------------------------- exact candidate evaluation
@@ -322,7 +383,7 @@ struct ListItem {
     int32_t kind, op, ca, cb;
 };
 
-__global__ __launch_bounds__(256) void k_score_list(const ListItem* __restrict__ items, int64_t m,
+__device__ __forceinline__ void d_score_list(const ListItem* __restrict__ items, int64_t m,
                                                     Ops o, const uint8_t* __restrict__ valid,
                                                     int n, int T, int mode,
                                                     const double* __restrict__ Yc,
@@ -360,6 +421,30 @@ __global__ __launch_bounds__(256) void k_score_list(const ListItem* __restrict__
     }
 }
 
+struct ListArgs {
+    const ListItem* items;
+    int64_t m;
+    Ops o;
+    const uint8_t* valid;
+    int n, T, mode;
+    const double *Yc, *syy;
+    int64_t N;
+    double* scores;
+    unsigned long long* nscored;
+    uint8_t* r2v;
+    double *r2m, *r2q;
+    int64_t off2, off3;
+};
+
+// grid (item blocks of 4, problems)
+__global__ __launch_bounds__(256) void k_score_list(ctab<ListArgs> A) {
+    const ListArgs& a = tab(A, blockIdx.y);
+    DSC_GLOBAL(a.items); DSC_GLOBAL(a.o.Vf); DSC_GLOBAL(a.o.Rf); DSC_GLOBAL(a.valid); DSC_GLOBAL(a.Yc); DSC_GLOBAL(a.syy); DSC_GLOBAL(a.scores); DSC_GLOBAL(a.nscored);
+    if ((int64_t)blockIdx.x * 4 >= a.m) return;
+    d_score_list(a.items, a.m, a.o, a.valid, a.n, a.T, a.mode, a.Yc, a.syy, a.N, a.scores, a.nscored,
+                 a.r2v, a.r2m, a.r2q, a.off2, a.off3);
+}
+
 // --------------------------------------------------- streamed pair screen
 // Tile of one wave: J operand features j (uniform) x 64 operand features i
 // (one per lane).  For every (i, j) with i < j and every operator of OPS,
@@ -370,9 +455,8 @@ __global__ __launch_bounds__(256) void k_score_list(const ListItem* __restrict__
 //
 // OPS bits: 0 add, 1 sub, 2 mul, 3 div, 4 rdiv.
 struct PairArgs {
-    const int2* tiles;        // (jc0, ic0) per wave (dense) or (jc, list offset)
+    const int2* tiles;        // precision form: (jc, ic0) per wave
     const int32_t* ilist;     // explicit partner lists (list mode) or NULL
-    const int32_t* icount;    // per-wave partner count (list mode)
     int64_t n_tiles;
     int n, ldm, ldn, Mc, jc_end, i_end;   // i_end: end of the partner pool
     const double *Vs, *Rs, *Cs, *Vf, *Rf, *Cf, *mu, *mur;
@@ -400,26 +484,31 @@ struct PairArgs {
 // wave 1 + wave 2 + wave 3), so results do not depend on scheduling.
 constexpr int PAIR_SPLIT = 4;
 
+// Tiles of every problem of a call form one list, heaviest first:
+// (problem, jc0, ic0, -) dense or (problem, jc, list offset, count) in list
+// mode; the problem's arguments are read from A.
 template <int OPS, int J, int TP, bool LIST>
-__global__ __launch_bounds__(256) void k_screen_pairs(PairArgs g) {
+__global__ __launch_bounds__(256) void k_screen_pairs(ctab<PairArgs> A,
+                                                      const int4* __restrict__ tiles) {
     constexpr int NOP = ((OPS >> 0) & 1) + ((OPS >> 1) & 1) + ((OPS >> 2) & 1) +
                         ((OPS >> 3) & 1) + ((OPS >> 4) & 1);
     constexpr int NV = J * NOP * (2 + TP);       // accumulators per lane
     constexpr int SL = 8;                        // accumulators combined per LDS round
     __shared__ double red[PAIR_SPLIT - 1][SL][64];
-    const int64_t w = blockIdx.x;
-    if (w >= g.n_tiles) return;
+    const int4 tile = tiles[blockIdx.x];
+    const PairArgs& g = tab(A, tile.x);
+    DSC_GLOBAL(g.ilist); DSC_GLOBAL(g.Vs); DSC_GLOBAL(g.Rs); DSC_GLOBAL(g.Cs); DSC_GLOBAL(g.Vf); DSC_GLOBAL(g.Rf); DSC_GLOBAL(g.Cf); DSC_GLOBAL(g.mu); DSC_GLOBAL(g.mur); DSC_GLOBAL(g.valid);
+    DSC_GLOBAL(g.mat_raw); DSC_GLOBAL(g.Yn); DSC_GLOBAL(g.ysum); DSC_GLOBAL(g.scores); DSC_GLOBAL(g.nscored); DSC_GLOBAL(g.fix_ids); DSC_GLOBAL(g.fix_cnt); DSC_GLOBAL(g.msq);
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    const int2 tile = g.tiles[w];
-    const int jc0 = tile.x;
+    const int jc0 = tile.y;
     int i;
     bool lane_ok;
     if (LIST) {
-        lane_ok = lane < g.icount[w];
-        i = g.ilist[tile.y + (lane_ok ? lane : 0)];
+        lane_ok = lane < tile.w;
+        i = g.ilist[tile.z + (lane_ok ? lane : 0)];
     } else {
-        i = tile.y + lane;
+        i = tile.z + lane;
         lane_ok = i < g.i_end;
     }
     const int ic = lane_ok ? i : 0;
@@ -1074,7 +1163,7 @@ __global__ __launch_bounds__(256) void k_screen_lp(PairArgs g, const void* __res
 
 // ------------------------------------------------------------ selection
 // Pool = every candidate whose score may reach theta - margin.
-__global__ __launch_bounds__(256) void k_compact(const double* __restrict__ sc, int64_t N,
+__device__ __forceinline__ void d_compact(const double* __restrict__ sc, int64_t N,
                                                  const uint32_t* __restrict__ sel,
                                                  const int64_t* __restrict__ st, double margin,
                                                  int64_t cap, int64_t* __restrict__ pool,
@@ -1094,9 +1183,9 @@ __global__ __launch_bounds__(256) void k_compact(const double* __restrict__ sc, 
 // Exact FP64 rescore of the pool (one wave per entry); also flags entries
 // whose ID is excluded.
 template <int TMAX>
-__global__ __launch_bounds__(256) void k_rescore(const int64_t* __restrict__ pool,
+__device__ __forceinline__ void d_rescore(const int64_t* __restrict__ pool,
                                                  const unsigned long long* __restrict__ Pp, int64_t cap,
-                                                 EvalCtx ev, Ops o, int n,
+                                                 const EvalCtx& ev, Ops o, int n,
                                                  int T, int mode, int tlist,
                                                  const double* __restrict__ Yc,
                                                  const double* __restrict__ syy,
@@ -1139,9 +1228,9 @@ __global__ __launch_bounds__(256) void k_rescore(const int64_t* __restrict__ poo
 // Exact two-pass score of the candidates whose shifted one-pass moments
 // were ill-conditioned (one wave each), written back into the score slots.
 template <int TMAX>
-__global__ __launch_bounds__(256) void k_fixup(const int64_t* __restrict__ ids,
+__device__ __forceinline__ void d_fixup(const int64_t* __restrict__ ids,
                                                const unsigned long long* __restrict__ cnt,
-                                               int64_t cap, EvalCtx ev, Ops o, int n,
+                                               int64_t cap, const EvalCtx& ev, Ops o, int n,
                                                int T, int mode, const double* __restrict__ Yc,
                                                const double* __restrict__ syy, int64_t N,
                                                double* __restrict__ scores,
@@ -1173,7 +1262,7 @@ __global__ __launch_bounds__(256) void k_fixup(const int64_t* __restrict__ ids,
 }
 
 // Rank sort of the pool by (-score, ID).
-__global__ __launch_bounds__(256) void k_rank(const double* __restrict__ ps,
+__device__ __forceinline__ void d_rank(const double* __restrict__ ps,
                                               const int64_t* __restrict__ pool,
                                               const unsigned long long* __restrict__ Pp, int64_t cap,
                                               int32_t* __restrict__ order) {
@@ -1200,7 +1289,7 @@ __global__ __launch_bounds__(256) void k_rank(const double* __restrict__ ps,
 
 // Near-tie window of each sorted entry: lo[q] = first earlier position whose
 // score is within TAU_NEAR (relative) of entry q, scanning backwards.
-__global__ void k_window(const double* __restrict__ ps, const int32_t* __restrict__ order,
+__device__ __forceinline__ void d_window(const double* __restrict__ ps, const int32_t* __restrict__ order,
                          const unsigned long long* __restrict__ Pp, int64_t cap,
                          int32_t* __restrict__ lo, int32_t* __restrict__ cnt) {
     const int64_t P = min((int64_t)*Pp, cap);
@@ -1220,7 +1309,7 @@ __global__ void k_window(const double* __restrict__ ps, const int32_t* __restric
 }
 
 // Exclusive prefix sum of cnt (single block).
-__global__ __launch_bounds__(1024) void k_scan_offsets(const int32_t* __restrict__ cnt,
+__device__ __forceinline__ void d_scan_offsets(const int32_t* __restrict__ cnt,
                                                        const unsigned long long* __restrict__ Pp,
                                                        int64_t cap, int64_t* __restrict__ off) {
     const int64_t P = min((int64_t)*Pp, cap);
@@ -1250,12 +1339,12 @@ __global__ __launch_bounds__(1024) void k_scan_offsets(const int32_t* __restrict
 
 // One wave per near-tie pair (earlier position lo[q]+k, later position q):
 // duplicate flag = |corr| >= 1 - TAU_DUP.
-__global__ __launch_bounds__(256) void k_pairs(const int64_t* __restrict__ pool,
+__device__ __forceinline__ void d_pairs(const int64_t* __restrict__ pool,
                                                const int32_t* __restrict__ order,
                                                const int32_t* __restrict__ lo,
                                                const int64_t* __restrict__ off,
                                                const unsigned long long* __restrict__ Pp, int64_t cap,
-                                               EvalCtx ev, Ops o, int n,
+                                               const EvalCtx& ev, Ops o, int n,
                                                uint8_t* __restrict__ flag, int64_t flag_cap) {
     const int64_t P = min((int64_t)*Pp, cap);
     const int64_t total = min(off[P], flag_cap);
@@ -1323,7 +1412,7 @@ __device__ __forceinline__ int64_t block_excl_scan(int64_t v, int64_t* part) {
     return incl - v;
 }
 
-__global__ __launch_bounds__(GRP_THREADS) void k_groups(
+__device__ __forceinline__ void d_groups(
     const int64_t* __restrict__ pool, const double* __restrict__ ps, const uint8_t* __restrict__ pex,
     const int32_t* __restrict__ order, const int32_t* __restrict__ lo, const int64_t* __restrict__ off,
     const uint8_t* __restrict__ flag, const unsigned long long* __restrict__ Pp, int64_t cap,
@@ -1464,7 +1553,7 @@ __global__ __launch_bounds__(GRP_THREADS) void k_groups(
 // in LDS, one block of 1024 threads.
 constexpr int BITONIC_MAX = 4096;
 
-__global__ __launch_bounds__(1024) void k_bitonic(const double* __restrict__ ps,
+__device__ __forceinline__ void d_bitonic(const double* __restrict__ ps,
                                                   const int64_t* __restrict__ pool,
                                                   const unsigned long long* __restrict__ Pp,
                                                   int64_t cap, int32_t* __restrict__ order) {
@@ -1502,8 +1591,8 @@ __global__ __launch_bounds__(1024) void k_bitonic(const double* __restrict__ ps,
 }
 
 // Values of the selected candidates: one wave per output row.
-__global__ __launch_bounds__(256) void k_values(const int64_t* __restrict__ ids, int64_t m,
-                                                EvalCtx ev, Ops o, int n,
+__device__ __forceinline__ void d_values(const int64_t* __restrict__ ids, int64_t m,
+                                                const EvalCtx& ev, Ops o, int n,
                                                 double* __restrict__ out, int64_t ldv) {
     const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (w >= m) return;
@@ -1515,55 +1604,177 @@ __global__ __launch_bounds__(256) void k_values(const int64_t* __restrict__ ids,
         out[w * ldv + i] = ok ? cand_value(c, o, i) : __longlong_as_double(0x7FF8000000000000LL);
 }
 
+// ------------------------------------------------- batched kernel entries
+// Exact re-decisions of one problem (ill-conditioned shifted moments).
+struct FixArgs {
+    const int64_t* ids;
+    const unsigned long long* cnt;
+    int64_t cap;
+    EvalCtx ev;
+    Ops o;
+    int n, T, mode;
+    const double *Yc, *syy;
+    int64_t N;
+    double* scores;
+    unsigned long long* nscored;
+    uint8_t* r2v;
+    double *r2m, *r2q;
+};
+
+// grid (persistent blocks, problems)
+__global__ __launch_bounds__(256) void k_fixup(ctab<FixArgs> A) {
+    const FixArgs& a = tab(A, blockIdx.y);
+    DSC_GLOBAL(a.ids); DSC_GLOBAL(a.cnt); DSC_GLOBAL(a.ev.raw2c); DSC_GLOBAL(a.ev.valid); DSC_GLOBAL(a.o.Vf); DSC_GLOBAL(a.o.Rf); DSC_GLOBAL(a.Yc); DSC_GLOBAL(a.syy); DSC_GLOBAL(a.scores); DSC_GLOBAL(a.nscored);
+    d_fixup<DISCOVER_MAX_TARGETS>(a.ids, a.cnt, a.cap, a.ev, a.o, a.n, a.T, a.mode, a.Yc, a.syy, a.N,
+                                  a.scores, a.nscored, a.r2v, a.r2m, a.r2q);
+}
+
+// Everything the exact top-k of one list (problem, target) works on.
+struct SelArgs {
+    const double* sc;         // score slots of the list
+    int64_t N;
+    const uint32_t* sel;      // radix selection of the list
+    const int64_t* st;
+    double margin;
+    int64_t cap, fcap;        // pool and duplicate-pair capacities
+    int64_t* pool;
+    unsigned long long* cnt;  // pool entries found (may exceed cap)
+    EvalCtx ev;
+    Ops o;
+    int n, T, mode, t, k, dedup;
+    const double *Yc, *syy;
+    const int64_t* excl;
+    int n_excl;
+    double* ps;
+    uint8_t* pex;
+    unsigned long long* maxerr;
+    int32_t *order, *lo, *wc;
+    int64_t* off;
+    uint8_t* flag;
+    int32_t *parent, *blk;
+    unsigned long long* repid;
+    int32_t *reppos, *headpos;
+    int64_t* out_ids;
+    double* out_sc;
+    int64_t* res;
+};
+
+// grid (blocks, lists) for the streaming kernels, (lists) for the one-block ones
+__global__ __launch_bounds__(256) void k_compact(ctab<SelArgs> A) {
+    const SelArgs& a = tab(A, blockIdx.y);
+    DSC_GLOBAL(a.sc); DSC_GLOBAL(a.sel); DSC_GLOBAL(a.st); DSC_GLOBAL(a.pool); DSC_GLOBAL(a.cnt); DSC_GLOBAL(a.ev.raw2c); DSC_GLOBAL(a.ev.valid); DSC_GLOBAL(a.o.Vf); DSC_GLOBAL(a.o.Rf); DSC_GLOBAL(a.Yc); DSC_GLOBAL(a.syy); DSC_GLOBAL(a.ps); DSC_GLOBAL(a.pex); DSC_GLOBAL(a.maxerr); DSC_GLOBAL(a.order); DSC_GLOBAL(a.lo); DSC_GLOBAL(a.wc); DSC_GLOBAL(a.off); DSC_GLOBAL(a.flag); DSC_GLOBAL(a.parent); DSC_GLOBAL(a.blk); DSC_GLOBAL(a.repid); DSC_GLOBAL(a.reppos); DSC_GLOBAL(a.headpos); DSC_GLOBAL(a.out_ids); DSC_GLOBAL(a.out_sc); DSC_GLOBAL(a.res);
+    d_compact(a.sc, a.N, a.sel, a.st, a.margin, a.cap, a.pool, a.cnt);
+}
+
+__global__ __launch_bounds__(256) void k_rescore(ctab<SelArgs> A) {
+    const SelArgs& a = tab(A, blockIdx.y);
+    DSC_GLOBAL(a.sc); DSC_GLOBAL(a.sel); DSC_GLOBAL(a.st); DSC_GLOBAL(a.pool); DSC_GLOBAL(a.cnt); DSC_GLOBAL(a.ev.raw2c); DSC_GLOBAL(a.ev.valid); DSC_GLOBAL(a.o.Vf); DSC_GLOBAL(a.o.Rf); DSC_GLOBAL(a.Yc); DSC_GLOBAL(a.syy); DSC_GLOBAL(a.ps); DSC_GLOBAL(a.pex); DSC_GLOBAL(a.maxerr); DSC_GLOBAL(a.order); DSC_GLOBAL(a.lo); DSC_GLOBAL(a.wc); DSC_GLOBAL(a.off); DSC_GLOBAL(a.flag); DSC_GLOBAL(a.parent); DSC_GLOBAL(a.blk); DSC_GLOBAL(a.repid); DSC_GLOBAL(a.reppos); DSC_GLOBAL(a.headpos); DSC_GLOBAL(a.out_ids); DSC_GLOBAL(a.out_sc); DSC_GLOBAL(a.res);
+    d_rescore<DISCOVER_MAX_TARGETS>(a.pool, a.cnt, a.cap, a.ev, a.o, a.n, a.T, a.mode, a.t, a.Yc, a.syy,
+                                    a.excl, a.n_excl, a.ps, a.pex, a.sc, a.maxerr);
+}
+
+__global__ __launch_bounds__(1024) void k_bitonic(ctab<SelArgs> A) {
+    const SelArgs& a = tab(A, blockIdx.x);
+    DSC_GLOBAL(a.sc); DSC_GLOBAL(a.sel); DSC_GLOBAL(a.st); DSC_GLOBAL(a.pool); DSC_GLOBAL(a.cnt); DSC_GLOBAL(a.ev.raw2c); DSC_GLOBAL(a.ev.valid); DSC_GLOBAL(a.o.Vf); DSC_GLOBAL(a.o.Rf); DSC_GLOBAL(a.Yc); DSC_GLOBAL(a.syy); DSC_GLOBAL(a.ps); DSC_GLOBAL(a.pex); DSC_GLOBAL(a.maxerr); DSC_GLOBAL(a.order); DSC_GLOBAL(a.lo); DSC_GLOBAL(a.wc); DSC_GLOBAL(a.off); DSC_GLOBAL(a.flag); DSC_GLOBAL(a.parent); DSC_GLOBAL(a.blk); DSC_GLOBAL(a.repid); DSC_GLOBAL(a.reppos); DSC_GLOBAL(a.headpos); DSC_GLOBAL(a.out_ids); DSC_GLOBAL(a.out_sc); DSC_GLOBAL(a.res);
+    d_bitonic(a.ps, a.pool, a.cnt, a.cap, a.order);
+}
+
+__global__ __launch_bounds__(256) void k_rank(ctab<SelArgs> A) {
+    const SelArgs& a = tab(A, blockIdx.y);
+    DSC_GLOBAL(a.sc); DSC_GLOBAL(a.sel); DSC_GLOBAL(a.st); DSC_GLOBAL(a.pool); DSC_GLOBAL(a.cnt); DSC_GLOBAL(a.ev.raw2c); DSC_GLOBAL(a.ev.valid); DSC_GLOBAL(a.o.Vf); DSC_GLOBAL(a.o.Rf); DSC_GLOBAL(a.Yc); DSC_GLOBAL(a.syy); DSC_GLOBAL(a.ps); DSC_GLOBAL(a.pex); DSC_GLOBAL(a.maxerr); DSC_GLOBAL(a.order); DSC_GLOBAL(a.lo); DSC_GLOBAL(a.wc); DSC_GLOBAL(a.off); DSC_GLOBAL(a.flag); DSC_GLOBAL(a.parent); DSC_GLOBAL(a.blk); DSC_GLOBAL(a.repid); DSC_GLOBAL(a.reppos); DSC_GLOBAL(a.headpos); DSC_GLOBAL(a.out_ids); DSC_GLOBAL(a.out_sc); DSC_GLOBAL(a.res);
+    if ((int64_t)blockIdx.x * 256 >= min((int64_t)*a.cnt, a.cap)) return;
+    d_rank(a.ps, a.pool, a.cnt, a.cap, a.order);
+}
+
+__global__ __launch_bounds__(256) void k_window(ctab<SelArgs> A) {
+    const SelArgs& a = tab(A, blockIdx.y);
+    DSC_GLOBAL(a.sc); DSC_GLOBAL(a.sel); DSC_GLOBAL(a.st); DSC_GLOBAL(a.pool); DSC_GLOBAL(a.cnt); DSC_GLOBAL(a.ev.raw2c); DSC_GLOBAL(a.ev.valid); DSC_GLOBAL(a.o.Vf); DSC_GLOBAL(a.o.Rf); DSC_GLOBAL(a.Yc); DSC_GLOBAL(a.syy); DSC_GLOBAL(a.ps); DSC_GLOBAL(a.pex); DSC_GLOBAL(a.maxerr); DSC_GLOBAL(a.order); DSC_GLOBAL(a.lo); DSC_GLOBAL(a.wc); DSC_GLOBAL(a.off); DSC_GLOBAL(a.flag); DSC_GLOBAL(a.parent); DSC_GLOBAL(a.blk); DSC_GLOBAL(a.repid); DSC_GLOBAL(a.reppos); DSC_GLOBAL(a.headpos); DSC_GLOBAL(a.out_ids); DSC_GLOBAL(a.out_sc); DSC_GLOBAL(a.res);
+    d_window(a.ps, a.order, a.cnt, a.cap, a.lo, a.wc);
+}
+
+__global__ __launch_bounds__(1024) void k_scan_offsets(ctab<SelArgs> A) {
+    const SelArgs& a = tab(A, blockIdx.x);
+    DSC_GLOBAL(a.sc); DSC_GLOBAL(a.sel); DSC_GLOBAL(a.st); DSC_GLOBAL(a.pool); DSC_GLOBAL(a.cnt); DSC_GLOBAL(a.ev.raw2c); DSC_GLOBAL(a.ev.valid); DSC_GLOBAL(a.o.Vf); DSC_GLOBAL(a.o.Rf); DSC_GLOBAL(a.Yc); DSC_GLOBAL(a.syy); DSC_GLOBAL(a.ps); DSC_GLOBAL(a.pex); DSC_GLOBAL(a.maxerr); DSC_GLOBAL(a.order); DSC_GLOBAL(a.lo); DSC_GLOBAL(a.wc); DSC_GLOBAL(a.off); DSC_GLOBAL(a.flag); DSC_GLOBAL(a.parent); DSC_GLOBAL(a.blk); DSC_GLOBAL(a.repid); DSC_GLOBAL(a.reppos); DSC_GLOBAL(a.headpos); DSC_GLOBAL(a.out_ids); DSC_GLOBAL(a.out_sc); DSC_GLOBAL(a.res);
+    d_scan_offsets(a.wc, a.cnt, a.cap, a.off);
+}
+
+__global__ __launch_bounds__(256) void k_pairs(ctab<SelArgs> A) {
+    const SelArgs& a = tab(A, blockIdx.y);
+    DSC_GLOBAL(a.sc); DSC_GLOBAL(a.sel); DSC_GLOBAL(a.st); DSC_GLOBAL(a.pool); DSC_GLOBAL(a.cnt); DSC_GLOBAL(a.ev.raw2c); DSC_GLOBAL(a.ev.valid); DSC_GLOBAL(a.o.Vf); DSC_GLOBAL(a.o.Rf); DSC_GLOBAL(a.Yc); DSC_GLOBAL(a.syy); DSC_GLOBAL(a.ps); DSC_GLOBAL(a.pex); DSC_GLOBAL(a.maxerr); DSC_GLOBAL(a.order); DSC_GLOBAL(a.lo); DSC_GLOBAL(a.wc); DSC_GLOBAL(a.off); DSC_GLOBAL(a.flag); DSC_GLOBAL(a.parent); DSC_GLOBAL(a.blk); DSC_GLOBAL(a.repid); DSC_GLOBAL(a.reppos); DSC_GLOBAL(a.headpos); DSC_GLOBAL(a.out_ids); DSC_GLOBAL(a.out_sc); DSC_GLOBAL(a.res);
+    if (!a.dedup) return;
+    d_pairs(a.pool, a.order, a.lo, a.off, a.cnt, a.cap, a.ev, a.o, a.n, a.flag, a.fcap);
+}
+
+__global__ __launch_bounds__(GRP_THREADS) void k_groups(ctab<SelArgs> A) {
+    const SelArgs& a = tab(A, blockIdx.x);
+    DSC_GLOBAL(a.sc); DSC_GLOBAL(a.sel); DSC_GLOBAL(a.st); DSC_GLOBAL(a.pool); DSC_GLOBAL(a.cnt); DSC_GLOBAL(a.ev.raw2c); DSC_GLOBAL(a.ev.valid); DSC_GLOBAL(a.o.Vf); DSC_GLOBAL(a.o.Rf); DSC_GLOBAL(a.Yc); DSC_GLOBAL(a.syy); DSC_GLOBAL(a.ps); DSC_GLOBAL(a.pex); DSC_GLOBAL(a.maxerr); DSC_GLOBAL(a.order); DSC_GLOBAL(a.lo); DSC_GLOBAL(a.wc); DSC_GLOBAL(a.off); DSC_GLOBAL(a.flag); DSC_GLOBAL(a.parent); DSC_GLOBAL(a.blk); DSC_GLOBAL(a.repid); DSC_GLOBAL(a.reppos); DSC_GLOBAL(a.headpos); DSC_GLOBAL(a.out_ids); DSC_GLOBAL(a.out_sc); DSC_GLOBAL(a.res);
+    d_groups(a.pool, a.ps, a.pex, a.order, a.lo, a.off, a.flag, a.cnt, a.cap, a.fcap, a.k, a.dedup,
+             a.sel, a.st, a.margin, a.parent, a.blk, a.repid, a.reppos, a.headpos, a.out_ids,
+             a.out_sc, a.res);
+}
+
+// Values of the selected features of one list.
+struct ValArgs {
+    const int64_t* ids;
+    int64_t m;
+    EvalCtx ev;
+    Ops o;
+    int n;
+    double* out;
+    int64_t ldv;
+};
+
+// grid (row blocks of 4, lists)
+__global__ __launch_bounds__(256) void k_values(ctab<ValArgs> A) {
+    const ValArgs& a = tab(A, blockIdx.y);
+    DSC_GLOBAL(a.ids); DSC_GLOBAL(a.ev.raw2c); DSC_GLOBAL(a.ev.valid); DSC_GLOBAL(a.o.Vf); DSC_GLOBAL(a.o.Rf); DSC_GLOBAL(a.out);
+    if ((int64_t)blockIdx.x * 4 >= a.m) return;
+    d_values(a.ids, a.m, a.ev, a.o, a.n, a.out, a.ldv);
+}
+
 }  // namespace dsc
 
 // ====================================================================== host
 namespace dsc {
 
-template <class T>
-static T download1(const T* src, hipStream_t st) {
-    T v;
-    DSC_HIP(hipMemcpyAsync(&v, src, sizeof(T), hipMemcpyDeviceToHost, st));
-    DSC_HIP(hipStreamSynchronize(st));
-    return v;
-}
-
 static int pad_targets(int T) { return T <= 1 ? 1 : T <= 2 ? 2 : T <= 4 ? 4 : T <= 8 ? 8 : 16; }
-
-template <int OPS, int J, int TP>
-static void launch_pairs_t(const PairArgs& a, bool list, hipStream_t st) {
-    const int64_t blocks = a.n_tiles;          // one 256-thread block per tile
-    if (blocks == 0) return;
-    if (list) k_screen_pairs<OPS, 1, TP, true><<<(unsigned)blocks, 256, 0, st>>>(a);
-    else k_screen_pairs<OPS, J, TP, false><<<(unsigned)blocks, 256, 0, st>>>(a);
-}
-
-template <int OPS>
-static void launch_pairs_ops(const PairArgs& a, bool list, int TP, int J, hipStream_t st) {
-    switch (TP) {
-    case 1:
-        if (J == 4) launch_pairs_t<OPS, 4, 1>(a, list, st);
-        else if (J == 2) launch_pairs_t<OPS, 2, 1>(a, list, st);
-        else launch_pairs_t<OPS, 1, 1>(a, list, st);
-        break;
-    case 2:
-        if (J == 2) launch_pairs_t<OPS, 2, 2>(a, list, st);
-        else launch_pairs_t<OPS, 1, 2>(a, list, st);
-        break;
-    case 4: launch_pairs_t<OPS, 1, 4>(a, list, st); break;
-    case 8: launch_pairs_t<OPS, 1, 8>(a, list, st); break;
-    default: launch_pairs_t<OPS, 1, 16>(a, list, st); break;
-    }
-}
 
 // Tile widths J (operand features j per wave) the dense kernel is built for.
 static int max_J(int TP) { return TP == 1 ? 4 : TP == 2 ? 2 : 1; }
 
-static void launch_pairs(int OPS, const PairArgs& a, bool list, int TP, int J, hipStream_t st) {
+template <int OPS, int J, int TP>
+static void launch_pairs_t(ctab<PairArgs> A, const int4* tiles, int64_t n, bool list,
+                           hipStream_t st) {
+    if (n == 0) return;                        // one 256-thread block per tile
+    if (list) k_screen_pairs<OPS, 1, TP, true><<<(unsigned)n, 256, 0, st>>>(A, tiles);
+    else k_screen_pairs<OPS, J, TP, false><<<(unsigned)n, 256, 0, st>>>(A, tiles);
+}
+
+template <int OPS>
+static void launch_pairs_ops(ctab<PairArgs> A, const int4* tiles, int64_t n, bool list, int TP,
+                             int J, hipStream_t st) {
+    switch (TP) {
+    case 1:
+        if (J == 4) launch_pairs_t<OPS, 4, 1>(A, tiles, n, list, st);
+        else if (J == 2) launch_pairs_t<OPS, 2, 1>(A, tiles, n, list, st);
+        else launch_pairs_t<OPS, 1, 1>(A, tiles, n, list, st);
+        break;
+    case 2:
+        if (J == 2) launch_pairs_t<OPS, 2, 2>(A, tiles, n, list, st);
+        else launch_pairs_t<OPS, 1, 2>(A, tiles, n, list, st);
+        break;
+    case 4: launch_pairs_t<OPS, 1, 4>(A, tiles, n, list, st); break;
+    case 8: launch_pairs_t<OPS, 1, 8>(A, tiles, n, list, st); break;
+    default: launch_pairs_t<OPS, 1, 16>(A, tiles, n, list, st); break;
+    }
+}
+
+static void launch_pairs(int OPS, ctab<PairArgs> A, const int4* tiles, int64_t n, bool list, int TP,
+                         int J, hipStream_t st) {
     switch (OPS) {
-    case 31: launch_pairs_ops<31>(a, list, TP, J, st); break;
-    case 28: launch_pairs_ops<28>(a, list, TP, J, st); break;
-    case 3: launch_pairs_ops<3>(a, list, TP, J, st); break;
+    case 31: launch_pairs_ops<31>(A, tiles, n, list, TP, J, st); break;
+    case 28: launch_pairs_ops<28>(A, tiles, n, list, TP, J, st); break;
+    case 3: launch_pairs_ops<3>(A, tiles, n, list, TP, J, st); break;
     default: DSC_FAIL(DISCOVER_E_UNSUPPORTED, "operator class %d", OPS);
     }
 }
@@ -1588,11 +1799,13 @@ static double lowprec_delta(int precision, int n) {
     return d;
 }
 
-// Device-resident description of one search space and its work lists,
-// cached in the context: it depends only on (p, n, units, parameters).
+// Description of one search space and its work lists, cached in the
+// context: it depends only on (p, units, parameters, padded target count),
+// not on the samples.  Device arrays hold what the kernels index directly;
+// tile lists stay on the host and are merged per call across problems.
 struct Plan {
     Space sp;
-    int n = 0, TP = 1, ldn = 0, ldm = 0;
+    int TP = 1, ldm = 0;
     std::vector<void*> allocs;
     int32_t* raw2c = nullptr;
     int64_t* mat_raw = nullptr;
@@ -1600,24 +1813,20 @@ struct Plan {
     int32_t *mat_a = nullptr, *mat_b = nullptr;
     ListItem* items = nullptr;
     int64_t n_items = 0;
-    int2* dtilesJ[3] = {nullptr, nullptr, nullptr};   // dense tiles for J = 1, 2, 4
-    int64_t n_dtilesJ[3] = {0, 0, 0};
-    int tuned_J = 0;                                     // 0: not tuned yet
-    double tune_ms[3] = {0, 0, 0};
+    std::vector<int2> dtilesJ[3];             // dense (jc0, ic0) tiles for J = 1, 2, 4
+    int tuned_J = 0;                          // 0: not tuned yet (single-problem calls)
     uint32_t dense_ops = 0;
     int dense_cls = 0;
     int2* ptiles = nullptr;                   // (j, i0) tiles of one j for the precision form
     int64_t n_ptiles = 0;
-    int2* ltiles = nullptr;
-    int32_t *ilist = nullptr, *icount = nullptr;
-    int64_t n_ltiles = 0;
+    std::vector<int4> ltiles;                 // list mode: (jc, list offset, count)
+    int32_t* ilist = nullptr;
     uint32_t list_ops = 0;
     int4* r3tiles = nullptr;                  // rung-3 tiles over rung-2 operands
     int64_t n_r3tiles = 0;
     int32_t* mat_unit = nullptr;
     uint32_t r3_ops = 0;
-    std::vector<int2> h_ltiles;               // host copies used to derive rung-3 tiles
-    std::vector<int32_t> h_icount;
+    std::string key;
 
     template <class T>
     T* up(const std::vector<T>& v) {
@@ -1640,7 +1849,7 @@ static std::string plan_key(const discover_problem& pb, const discover_screen_pa
     k.append((const char*)prm.rung_ops, sizeof prm.rung_ops);
     k.append((const char*)prm.rung_pool, sizeof prm.rung_pool);
     k.append((const char*)&prm.precision, sizeof prm.precision);
-    const int32_t dims[4] = {pb.p, pb.n, pb.B, pad_targets(pb.T)};
+    const int32_t dims[3] = {pb.p, pb.B, pad_targets(pb.T)};
     k.append((const char*)dims, sizeof dims);
     if (pb.B && pb.units) k.append((const char*)pb.units, sizeof(int32_t) * pb.p * pb.B);
     return k;
@@ -1651,14 +1860,14 @@ static std::shared_ptr<Plan> get_plan(discover_ctx* ctx, const discover_problem&
     const std::string key = plan_key(pb, prm);
     auto it = ctx->plans.find(key);
     if (it != ctx->plans.end()) return std::static_pointer_cast<Plan>(it->second);
-    if (ctx->plans.size() >= 16) ctx->plans.clear();
+    if (ctx->capturing) DSC_FAIL(DISCOVER_E_CAPACITY, "search-space plan built during graph capture");
+    if (ctx->plans.size() >= 64) ctx->plans.clear();
     auto P = std::make_shared<Plan>();
+    P->key = key;
     Space& sp = P->sp;
     build_space(sp, pb.p, prm, pb.B, pb.units);
     const SpaceDev& sd = sp.d;
-    P->n = pb.n;
     P->TP = pad_targets(pb.T);
-    P->ldn = (int)((pb.n + 63) / 64 * 64);
     const int Mc = sp.Mc();
     P->ldm = (int)((Mc + 63) / 64 * 64);
     P->raw2c = P->up(sp.raw2c);
@@ -1698,13 +1907,11 @@ static std::shared_ptr<Plan> get_plan(discover_ctx* ctx, const discover_problem&
         for (int jx = 0; jx < 3; jx++) {
             const int J = 1 << jx;
             if (J > max_J(P->TP)) break;
-            std::vector<int2> tiles;
+            std::vector<int2>& tiles = P->dtilesJ[jx];
             for (int32_t j = jc0; j < jc1; j += J) {
                 const int32_t ilim = std::min<int32_t>(i_end, std::min<int32_t>(j + J - 1, jc1 - 1));
                 for (int32_t i0 = 0; i0 < ilim; i0 += 64) tiles.push_back(make_int2(j, i0));
             }
-            P->dtilesJ[jx] = P->up(tiles);
-            P->n_dtilesJ[jx] = (int64_t)tiles.size();
         }
         std::vector<int2> pt;
         for (int32_t j = jc0; j < jc1; j++) {
@@ -1714,9 +1921,8 @@ static std::shared_ptr<Plan> get_plan(discover_ctx* ctx, const discover_problem&
         P->ptiles = P->up(pt);
         P->n_ptiles = (int64_t)pt.size();
     }
+    std::vector<int32_t> il;
     if (P->list_ops) {
-        std::vector<int2> tiles;
-        std::vector<int32_t> il, ic;
         std::map<std::string, std::vector<int32_t>> by_unit;
         auto key_of = [&](int32_t c) {
             return std::string((const char*)&sp.mat_unit[(size_t)c * Bq], sizeof(int32_t) * Bq);
@@ -1729,24 +1935,16 @@ static std::shared_ptr<Plan> get_plan(discover_ctx* ctx, const discover_problem&
                 if (f != by_unit.end()) {
                     const auto& v = f->second;
                     for (size_t q = 0; q < v.size(); q += 64) {
-                        tiles.push_back(make_int2(c, (int)il.size()));
                         const int cnt = (int)std::min<size_t>(64, v.size() - q);
-                        ic.push_back(cnt);
+                        P->ltiles.push_back(make_int4(c, (int)il.size(), cnt, 0));
                         il.insert(il.end(), v.begin() + q, v.begin() + q + cnt);
                     }
                 }
             }
             if (pool == R - 1) by_unit[key_of(c)].push_back(c);
         }
-        P->ltiles = P->up(tiles);
-        P->ilist = P->up(il);
-        P->icount = P->up(ic);
-        P->n_ltiles = (int64_t)tiles.size();
-        if (sp.stream3) {            // keep the host copies for the rung-3 list tiles
-            P->h_ltiles = tiles;
-            P->h_icount = ic;
-        }
     }
+    P->ilist = P->up(il);
     if (sp.stream3) {
         // rung-3 candidates op3(i, j2): one wave per 64 rung-2 features j2
         std::vector<int4> t3;
@@ -1759,8 +1957,7 @@ static std::shared_ptr<Plan> get_plan(discover_ctx* ctx, const discover_problem&
             if (sd.block[2][o] < 0) continue;
             const bool addcls = o <= OP_SUB;
             if (units && addcls) {
-                for (size_t q = 0; q < P->h_ltiles.size(); q++)
-                    t3.push_back(make_int4(o, P->h_ltiles[q].x, P->h_ltiles[q].y, P->h_icount[q]));
+                for (const int4& q : P->ltiles) t3.push_back(make_int4(o, q.x, q.y, q.z));
             } else {
                 for (int32_t l = c0; l < c1; l++)
                     for (int32_t k0 = 0; k0 < l; k0 += 64) t3.push_back(make_int4(o, l, k0, -1));
@@ -1781,14 +1978,18 @@ static std::shared_ptr<Plan> get_plan(discover_ctx* ctx, const discover_problem&
 struct Problem {
     std::shared_ptr<Plan> plan;
     int n, T, Tl, TP, ldn, ldm, Mc;
+    int64_t N, fix_cap;
     double *Vf, *Rf, *Cf, *Vs, *Rs, *Cs, *mu, *mur, *msq, *Yc, *Yn, *syy, *ysum, *scores;
     uint8_t* valid;
-    int* bad;
-    unsigned long long* nscored;
+    unsigned long long* ctr;                  // [0] bad target (int), [1] fix count, [2] scored, [3] rung-3 fix count
+    int64_t *fix_ids, *fix_ids3;
     uint8_t* r2v = nullptr;                   // rung-2 operand statistics (streamed rung 3)
     double* r2m = nullptr;
     double* r2q = nullptr;
+    void* ylp = nullptr;
+    int ldl = 0;
     int tile_j = 0;                           // dense pair kernel width used (0: not run)
+    bool pairs = false;                       // streamed rung with pair operators
     EvalCtx ev() const {
         EvalCtx e;
         e.sd = plan->sp.d;
@@ -1799,320 +2000,487 @@ struct Problem {
         e.r2_valid = r2v;
         return e;
     }
+    Ops ops() const { return Ops{Vf, Rf, ldn}; }
 };
 
-// Materialise the operand features and screen every candidate into the
-// score slots (no host synchronisation).
-static void screen_problem(discover_ctx* ctx, const discover_problem& pb,
-                           const discover_screen_params& prm, Problem& P, hipStream_t st) {
-    P.plan = get_plan(ctx, pb, prm);
-    const Plan& pl = *P.plan;
-    const Space& sp = pl.sp;
-    const SpaceDev& sd = sp.d;
-    const int n = pb.n;
-    P.n = n;
-    P.T = pb.T;
-    P.Tl = prm.score_mode == DISCOVER_SCORE_MAX ? 1 : pb.T;
-    P.TP = pl.TP;
-    P.ldn = pl.ldn;
-    P.ldm = pl.ldm;
-    P.Mc = sp.Mc();
-    const int Mc = P.Mc, ldn = P.ldn, ldm = P.ldm;
-    const int64_t N = sp.n_raw();
+// Per-list selection state carried across rounds (and into a captured run).
+struct ListState {
+    int b, t;
+    int64_t K, cap, fcap;
+    bool done = false;
+};
 
-    P.Vf = ctx->buf<double>("Vf", (size_t)Mc * ldn);
-    P.Rf = ctx->buf<double>("Rf", (size_t)Mc * ldn);
-    P.Cf = ctx->buf<double>("Cf", (size_t)Mc * ldn);
-    P.mu = ctx->buf<double>("mu", Mc);
-    P.mur = ctx->buf<double>("mur", Mc);
-    P.msq = ctx->buf<double>("msq", Mc);
-    P.valid = ctx->buf<uint8_t>("valid", Mc);
-    P.Yc = ctx->buf<double>("Yc", (size_t)pb.T * ldn);
-    P.Yn = ctx->buf<double>("Yn", (size_t)P.TP * ldn);
-    P.syy = ctx->buf<double>("syy", pb.T);
-    P.ysum = ctx->buf<double>("ysum", P.TP);
-    // counters: [0] bad target, [1] fix-up count, [2] scored (as u64 slots)
-    unsigned long long* ctr = ctx->buf<unsigned long long>("screen_ctr", 4);
-    P.bad = (int*)ctr;
-    P.nscored = ctr + 2;
-    unsigned long long* fix_cnt = ctr + 1;
-    DSC_HIP(hipMemsetAsync(ctr, 0, 32, st));
-    DSC_HIP(hipMemsetAsync(P.Yn, 0, (size_t)P.TP * ldn * 8, st));
-    DSC_HIP(hipMemsetAsync(P.ysum, 0, (size_t)P.TP * 8, st));
-    k_targets<<<pb.T, 256, 0, st>>>(n, pb.T, pb.Y, pb.ldy, ldn, P.Yc, P.Yn, P.syy, P.ysum, P.bad);
+// Allocate every problem's working memory for one call.
+static void layout_problems(discover_ctx* ctx, const discover_problem* probs, int nb,
+                            const discover_screen_params& prm, std::vector<Problem>& PS) {
+    PS.resize(nb);
+    Arena ar;
+    std::vector<std::vector<size_t>> o(nb);
+    for (int b = 0; b < nb; b++) {
+        const discover_problem& pb = probs[b];
+        Problem& P = PS[b];
+        P.plan = get_plan(ctx, pb, prm);
+        const Plan& pl = *P.plan;
+        const Space& sp = pl.sp;
+        P.n = pb.n;
+        P.T = pb.T;
+        P.Tl = prm.score_mode == DISCOVER_SCORE_MAX ? 1 : pb.T;
+        P.TP = pl.TP;
+        P.ldn = (int)((pb.n + 63) / 64 * 64);
+        P.ldm = pl.ldm;
+        P.Mc = sp.Mc();
+        P.N = sp.n_raw();
+        P.fix_cap = std::min<int64_t>(P.N, (int64_t)1 << 22);
+        P.pairs = sp.streamed && (pl.dense_ops || pl.list_ops);
+        const size_t Mc = P.Mc, ldn = P.ldn, n = P.n, ldm = P.ldm;
+        auto& v = o[b];
+        for (int k = 0; k < 3; k++) v.push_back(ar.add(Mc * ldn * 8));          // Vf Rf Cf
+        for (int k = 0; k < 3; k++) v.push_back(ar.add(Mc * 8));                // mu mur msq
+        v.push_back(ar.add(Mc));                                               // valid
+        v.push_back(ar.add((size_t)P.T * ldn * 8));                            // Yc
+        v.push_back(ar.add((size_t)P.TP * ldn * 8));                           // Yn
+        v.push_back(ar.add((size_t)P.T * 8));                                  // syy
+        v.push_back(ar.add((size_t)P.TP * 8));                                 // ysum
+        v.push_back(ar.add(32));                                               // ctr
+        v.push_back(ar.add((size_t)P.Tl * P.N * 8));                           // scores
+        v.push_back(ar.add((size_t)P.fix_cap * 8));                            // fix_ids
+        v.push_back(ar.add(sp.stream3 ? (size_t)P.fix_cap * 8 : 8));           // fix_ids3
+        for (int k = 0; k < 3; k++) v.push_back(ar.add(P.pairs ? n * ldm * 8 : 8));  // Vs Rs Cs
+        const size_t L2 = sp.stream3 ? (size_t)sp.d.L[2] : 1;
+        v.push_back(ar.add(L2));                                               // r2v
+        v.push_back(ar.add(L2 * 8));                                           // r2m
+        v.push_back(ar.add(L2 * 8));                                           // r2q
+        P.ldl = (int)cdiv(P.n, 32) * 32;
+        v.push_back(ar.add(prm.precision != DISCOVER_FP64 ? (size_t)16 * P.ldl * 2 : 8));  // Ylp
+    }
+    char* base = (char*)ctx->raw("scr_arena", ar.total);
+    for (int b = 0; b < nb; b++) {
+        Problem& P = PS[b];
+        const auto& v = o[b];
+        int q = 0;
+        auto at = [&](void) { return base + v[q++]; };
+        P.Vf = (double*)at(); P.Rf = (double*)at(); P.Cf = (double*)at();
+        P.mu = (double*)at(); P.mur = (double*)at(); P.msq = (double*)at();
+        P.valid = (uint8_t*)at();
+        P.Yc = (double*)at(); P.Yn = (double*)at(); P.syy = (double*)at(); P.ysum = (double*)at();
+        P.ctr = (unsigned long long*)at();
+        P.scores = (double*)at();
+        P.fix_ids = (int64_t*)at(); P.fix_ids3 = (int64_t*)at();
+        P.Vs = (double*)at(); P.Rs = (double*)at(); P.Cs = (double*)at();
+        uint8_t* r2v = (uint8_t*)at();
+        double* r2m = (double*)at();
+        double* r2q = (double*)at();
+        if (P.plan->sp.stream3) { P.r2v = r2v; P.r2m = r2m; P.r2q = r2q; }
+        P.ylp = at();
+    }
+}
+
+// Merged dense / list tiles of a call: problems in decreasing n (the
+// heaviest tiles first), each problem's tiles in plan order.
+struct TileGroup {
+    int cls, TP, J;
+    bool list;
+    std::vector<int4> tiles;
+};
+
+static std::vector<int> by_weight(const std::vector<Problem>& PS) {
+    std::vector<int> order(PS.size());
+    for (size_t b = 0; b < PS.size(); b++) order[b] = (int)b;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return PS[x].n > PS[y].n; });
+    return order;
+}
+
+// Autotuned tile width of a dense group: each admissible J is timed once
+// for this batch signature (every variant writes the same scores; the
+// counters the runs bump are restored), and the fastest is remembered.
+static int tune_dense(discover_ctx* ctx, const std::string& key, int cls, int TP,
+                      ctab<PairArgs> dA, std::vector<Problem>& PS, const std::vector<int>& members,
+                      hipStream_t st) {
+    auto it = ctx->tuned.find(key);
+    if (it != ctx->tuned.end()) return it->second;
+    if (ctx->capturing) DSC_FAIL(DISCOVER_E_CAPACITY, "tile autotuning during graph capture");
+    const std::vector<int> order = by_weight(PS);
+    std::vector<unsigned long long*> saved;
+    for (int b : members) {
+        unsigned long long* sv = ctx->buf<unsigned long long>("tune_ctr_" + std::to_string(b), 4);
+        DSC_HIP(hipMemcpyAsync(sv, PS[b].ctr, 32, hipMemcpyDeviceToDevice, st));
+        saved.push_back(sv);
+    }
+    double best = 1e30;
+    int bestJ = 1;
+    for (int jx = 0; jx < 3 && (1 << jx) <= max_J(TP); jx++) {
+        std::vector<int4> tiles;
+        for (int b : order) {
+            if (std::find(members.begin(), members.end(), b) == members.end()) continue;
+            for (const int2& t : PS[b].plan->dtilesJ[jx]) tiles.push_back(make_int4(b, t.x, t.y, 0));
+        }
+        const int4* dt = ctx->upload("tune_tiles", tiles, st);
+        hipEvent_t e0 = ctx->event(), e1 = ctx->event();
+        DSC_HIP(hipEventRecord(e0, st));
+        launch_pairs(cls, dA, dt, (int64_t)tiles.size(), false, TP, 1 << jx, st);
+        DSC_HIP(hipEventRecord(e1, st));
+        for (size_t q = 0; q < members.size(); q++)
+            DSC_HIP(hipMemcpyAsync(PS[members[q]].ctr, saved[q], 32, hipMemcpyDeviceToDevice, st));
+        DSC_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        DSC_HIP(hipEventElapsedTime(&ms, e0, e1));
+        ctx->free_events.push_back(e0);
+        ctx->free_events.push_back(e1);
+        if (ms < best) { best = ms; bestJ = 1 << jx; }
+    }
+    ctx->tuned[key] = bestJ;
+    return bestJ;
+}
+
+// Materialise the operand features of every problem and screen every
+// candidate into its score slots (no host synchronisation).
+static void screen_all(discover_ctx* ctx, const discover_problem* probs, int nb,
+                       const discover_screen_params& prm, std::vector<Problem>& PS, hipStream_t st) {
+    layout_problems(ctx, probs, nb, prm, PS);
+    // 1. fills: counters, padded target rows, score slots (NaN pattern), rung-2 flags
+    std::vector<FillSeg> fills;
+    for (Problem& P : PS) {
+        fills.push_back(fill_seg(P.ctr, 32, 0u));
+        fills.push_back(fill_seg(P.Yn, (size_t)P.TP * P.ldn * 8, 0u));
+        fills.push_back(fill_seg(P.ysum, (size_t)P.TP * 8, 0u));
+        fills.push_back(fill_seg(P.scores, (size_t)P.Tl * P.N * 8, 0xFFFFFFFFu));
+        if (P.r2v) fills.push_back(fill_seg(P.r2v, ((size_t)P.plan->sp.d.L[2] + 3) & ~size_t(3), 0u));
+    }
+    fill_all(ctx, "scr_fills", fills, st);
+    // 2. targets
+    std::vector<TgtArgs> ta(nb);
+    for (int b = 0; b < nb; b++) {
+        const Problem& P = PS[b];
+        ta[b] = TgtArgs{P.n, P.T, P.ldn, probs[b].Y, probs[b].ldy, P.Yc, P.Yn, P.syy, P.ysum, (int*)P.ctr};
+    }
+    k_targets<<<dim3(DISCOVER_MAX_TARGETS, nb), 256, 0, st>>>(ct(ctx->upload("scr_tgt", ta, st)));
     check_launch("k_targets");
+    // 3. operand features, rung by rung
+    std::vector<MatArgs> ma(nb);
+    int nlev = 0, nmax = 0;
+    std::vector<int> wmax(4, 0);
+    for (int b = 0; b < nb; b++) {
+        const Problem& P = PS[b];
+        const Plan& pl = *P.plan;
+        MatArgs& a = ma[b];
+        a = MatArgs{};
+        a.n = P.n; a.ldn = P.ldn;
+        a.nlev = (int)pl.sp.rung_start.size() - 1;
+        for (int r = 0; r <= a.nlev && r < 4; r++) a.rs[r] = pl.sp.rung_start[r];
+        a.X = probs[b].X; a.ldx = probs[b].ldx;
+        a.op = pl.mat_op; a.ca = pl.mat_a; a.cb = pl.mat_b; a.raw = pl.mat_raw;
+        a.Vf = P.Vf; a.Rf = P.Rf; a.Cf = P.Cf; a.mu = P.mu; a.mur = P.mur; a.msq = P.msq;
+        a.valid = P.valid;
+        nlev = std::max(nlev, a.nlev);
+        nmax = std::max(nmax, P.n);
+        for (int r = 0; r < a.nlev; r++) wmax[r] = std::max(wmax[r], a.rs[r + 1] - a.rs[r]);
+    }
+    const ctab<MatArgs> dma = ct(ctx->upload("scr_mat", ma, st));
     {
         KTimer kt(ctx, st, "materialise");
-        for (size_t r = 0; r + 1 < sp.rung_start.size(); r++) {
-            const int c0 = sp.rung_start[r], c1 = sp.rung_start[r + 1];
-            if (c1 <= c0) continue;
-            dim3 g((unsigned)cdiv(n, 256), (unsigned)(c1 - c0));
-            k_mat_values<<<g, 256, 0, st>>>(n, ldn, c0, c1, pb.X, pb.ldx, pl.mat_op, pl.mat_a,
-                                            pl.mat_b, pl.mat_raw, P.Vf);
-            k_mat_stats<<<(unsigned)cdiv(c1 - c0, 4), 256, 0, st>>>(
-                n, ldn, c0, c1, pl.mat_op, pl.mat_a, pl.mat_b, P.Vf, P.Rf, P.Cf, P.mu, P.mur, P.msq,
-                P.valid);
+        for (int r = 0; r < nlev; r++) {
+            if (!wmax[r]) continue;
+            k_mat_values<<<dim3((unsigned)cdiv(nmax, 256), (unsigned)wmax[r], nb), 256, 0, st>>>(dma, r);
+            k_mat_stats<<<dim3((unsigned)cdiv(wmax[r], 4), nb), 256, 0, st>>>(dma, r);
         }
         check_launch("k_mat");
     }
-    P.scores = ctx->buf<double>("scores", (size_t)P.Tl * N);
-    DSC_HIP(hipMemsetAsync(P.scores, 0xFF, (size_t)P.Tl * N * 8, st));
-    Ops ops{P.Vf, P.Rf, ldn};
-    const int64_t off2 = sp.stream3 ? sd.off[2] : 0, off3 = sp.stream3 ? sd.off[3] : 0;
-    if (sp.stream3) {
-        P.r2v = ctx->buf<uint8_t>("r2v", sd.L[2]);
-        P.r2m = ctx->buf<double>("r2m", sd.L[2]);
-        P.r2q = ctx->buf<double>("r2q", sd.L[2]);
-        DSC_HIP(hipMemsetAsync(P.r2v, 0, (size_t)sd.L[2], st));
+    // 4. exact list: operand features and unary candidates of the streamed rung
+    std::vector<ListArgs> la(nb);
+    int64_t mmax = 0;
+    for (int b = 0; b < nb; b++) {
+        const Problem& P = PS[b];
+        const Plan& pl = *P.plan;
+        const SpaceDev& sd = pl.sp.d;
+        ListArgs& a = la[b];
+        a = ListArgs{};
+        a.items = pl.items; a.m = pl.n_items; a.o = P.ops(); a.valid = P.valid;
+        a.n = P.n; a.T = P.T; a.mode = prm.score_mode; a.Yc = P.Yc; a.syy = P.syy; a.N = P.N;
+        a.scores = P.scores; a.nscored = P.ctr + 2;
+        a.r2v = P.r2v; a.r2m = P.r2m; a.r2q = P.r2q;
+        a.off2 = pl.sp.stream3 ? sd.off[2] : 0;
+        a.off3 = pl.sp.stream3 ? sd.off[3] : 0;
+        mmax = std::max(mmax, a.m);
     }
     {
         KTimer kt(ctx, st, "screen_list");
-        k_score_list<<<(unsigned)cdiv(pl.n_items, 4), 256, 0, st>>>(
-            pl.items, pl.n_items, ops, P.valid, n, pb.T, prm.score_mode, P.Yc, P.syy, N, P.scores,
-            P.nscored, P.r2v, P.r2m, P.r2q, off2, off3);
+        k_score_list<<<dim3((unsigned)cdiv(mmax, 4), nb), 256, 0, st>>>(ct(ctx->upload("scr_list", la, st)));
         check_launch("k_score_list");
     }
-    const int R = sp.streamed;
-    if (!R || (!pl.dense_ops && !pl.list_ops)) return;
-    P.Vs = ctx->buf<double>("Vs", (size_t)n * ldm);
-    P.Rs = ctx->buf<double>("Rs", (size_t)n * ldm);
-    P.Cs = ctx->buf<double>("Cs", (size_t)n * ldm);
-    {
-        dim3 g((unsigned)cdiv(n, 32), (unsigned)cdiv(Mc, 32)), b(32, 8);
-        k_transpose<<<g, b, 0, st>>>(n, Mc, ldn, ldm, P.Vf, P.Vs);
-        k_transpose<<<g, b, 0, st>>>(n, Mc, ldn, ldm, P.Rf, P.Rs);
-        k_transpose<<<g, b, 0, st>>>(n, Mc, ldn, ldm, P.Cf, P.Cs);
+    // 5. sample-major copies of the operands of the pair kernels
+    std::vector<TrArgs> tr;
+    std::vector<int> trb;
+    int tn = 0, tm = 0;
+    for (int b = 0; b < nb; b++) {
+        const Problem& P = PS[b];
+        if (!P.pairs) continue;
+        tr.push_back(TrArgs{P.n, P.Mc, P.ldn, P.ldm, {P.Vf, P.Rf, P.Cf}, {P.Vs, P.Rs, P.Cs}});
+        tn = std::max(tn, P.n);
+        tm = std::max(tm, P.Mc);
+    }
+    if (!tr.empty()) {
+        k_transpose<<<dim3((unsigned)cdiv(tn, 32), (unsigned)cdiv(tm, 32), (unsigned)(3 * tr.size())),
+                      dim3(32, 8), 0, st>>>(ct(ctx->upload("scr_tr", tr, st)));
         check_launch("k_transpose");
     }
-    const int pool = sd.pool[R];
-    PairArgs a{};
-    a.n = n; a.ldm = ldm; a.ldn = ldn; a.Mc = Mc; a.jc_end = sp.rung_start[R];
-    a.i_end = pool == R - 1 ? Mc : sp.rung_start[pool + 1];
-    a.Vs = P.Vs; a.Rs = P.Rs; a.Cs = P.Cs; a.Vf = P.Vf; a.Rf = P.Rf; a.Cf = P.Cf;
-    a.mu = P.mu; a.mur = P.mur; a.valid = P.valid; a.mat_raw = pl.mat_raw;
-    a.Yn = P.Yn; a.ysum = P.ysum; a.T = pb.T; a.mode = prm.score_mode; a.r = R;
-    a.sd = sd; a.N = N; a.scores = P.scores; a.nscored = P.nscored;
-    a.fix_cap = std::min<int64_t>(N, (int64_t)1 << 24);
-    a.fix_ids = ctx->buf<int64_t>("fix_ids", a.fix_cap);
-    a.fix_cnt = fix_cnt;
-    a.r2v = P.r2v;
-    a.r2m = P.r2m;
-    a.r2q = P.r2q;
-    a.msq = P.msq;
-    if (pl.dense_ops && prm.precision != DISCOVER_FP64) {
-        const int ldl = (int)cdiv(n, 32) * 32;
-        void* ylp = ctx->raw("Ylp", (size_t)16 * ldl * 2);
-        dim3 gy((unsigned)cdiv(ldl, 256), 16);
+    // 6. pair kernels
+    std::vector<PairArgs> pa(nb);
+    for (int b = 0; b < nb; b++) {
+        const Problem& P = PS[b];
+        const Plan& pl = *P.plan;
+        const Space& sp = pl.sp;
+        PairArgs& a = pa[b];
+        a = PairArgs{};
+        if (!P.pairs) continue;
+        const int R = sp.streamed;
+        const int pool = sp.d.pool[R];
+        a.n = P.n; a.ldm = P.ldm; a.ldn = P.ldn; a.Mc = P.Mc; a.jc_end = sp.rung_start[R];
+        a.i_end = pool == R - 1 ? P.Mc : sp.rung_start[pool + 1];
+        a.Vs = P.Vs; a.Rs = P.Rs; a.Cs = P.Cs; a.Vf = P.Vf; a.Rf = P.Rf; a.Cf = P.Cf;
+        a.mu = P.mu; a.mur = P.mur; a.valid = P.valid; a.mat_raw = pl.mat_raw;
+        a.Yn = P.Yn; a.ysum = P.ysum; a.T = P.T; a.mode = prm.score_mode; a.r = R;
+        a.sd = sp.d; a.N = P.N; a.scores = P.scores; a.nscored = P.ctr + 2;
+        a.fix_cap = P.fix_cap; a.fix_ids = P.fix_ids; a.fix_cnt = P.ctr + 1;
+        a.r2v = P.r2v; a.r2m = P.r2m; a.r2q = P.r2q; a.msq = P.msq;
+        a.ilist = pl.ilist;
+        a.opmask = pl.dense_ops;
+    }
+    const ctab<PairArgs> dpa = ct(ctx->upload("scr_pairs", pa, st));
+    const std::vector<int> order = by_weight(PS);
+    // 6a. precision form: per problem, MFMA screening with FP64 guard-band rescore
+    for (int b = 0; b < nb; b++) {
+        Problem& P = PS[b];
+        const Plan& pl = *P.plan;
+        if (!P.pairs || !pl.dense_ops || prm.precision == DISCOVER_FP64) continue;
         const bool fp16 = prm.precision == DISCOVER_FP16_GUARD;
-        if (fp16) k_targets_lp<true><<<gy, 256, 0, st>>>(n, pb.T, ldn, ldl, P.Yn, (_Float16*)ylp);
-        else k_targets_lp<false><<<gy, 256, 0, st>>>(n, pb.T, ldn, ldl, P.Yn, (__bf16*)ylp);
-        a.tiles = pl.ptiles; a.ilist = nullptr; a.icount = nullptr;
-        a.n_tiles = pl.n_ptiles; a.opmask = pl.dense_ops;
+        dim3 gy((unsigned)cdiv(P.ldl, 256), 16);
+        if (fp16) k_targets_lp<true><<<gy, 256, 0, st>>>(P.n, P.T, P.ldn, P.ldl, P.Yn, (_Float16*)P.ylp);
+        else k_targets_lp<false><<<gy, 256, 0, st>>>(P.n, P.T, P.ldn, P.ldl, P.Yn, (__bf16*)P.ylp);
+        PairArgs a = pa[b];
+        a.tiles = pl.ptiles; a.n_tiles = pl.n_ptiles;
         KTimer kt(ctx, st, "screen_lp");
-        if (fp16) launch_lp<true>(pl.dense_cls, a, ylp, ldl, st);
-        else launch_lp<false>(pl.dense_cls, a, ylp, ldl, st);
+        if (fp16) launch_lp<true>(pl.dense_cls, a, P.ylp, P.ldl, st);
+        else launch_lp<false>(pl.dense_cls, a, P.ylp, P.ldl, st);
         check_launch("k_screen_lp");
-    } else if (pl.dense_ops) {
-        a.ilist = nullptr; a.icount = nullptr; a.opmask = pl.dense_ops;
-        Plan& mp = *P.plan;
-        if (prm.tile_j <= 0 && mp.tuned_J == 0) {
-            // autotune the tile width once per plan: every variant writes the same
-            // scores (each candidate's sums run in the same order), so the timing
-            // runs only repeat idempotent stores; the counters they bump are
-            // restored after each run, and the fastest J is cached in the plan
-            unsigned long long* saved = ctx->buf<unsigned long long>("screen_ctr_tune", 4);
-            DSC_HIP(hipMemcpyAsync(saved, ctr, 32, hipMemcpyDeviceToDevice, st));
-            double best = 1e30;
-            for (int jx = 0; jx < 3 && (1 << jx) <= max_J(P.TP); jx++) {
-                a.tiles = mp.dtilesJ[jx];
-                a.n_tiles = mp.n_dtilesJ[jx];
-                hipEvent_t e0 = ctx->event(), e1 = ctx->event();
-                DSC_HIP(hipEventRecord(e0, st));
-                launch_pairs(pl.dense_cls, a, false, P.TP, 1 << jx, st);
-                DSC_HIP(hipEventRecord(e1, st));
-                DSC_HIP(hipMemcpyAsync(ctr, saved, 32, hipMemcpyDeviceToDevice, st));
-                DSC_HIP(hipEventSynchronize(e1));
-                float ms = 0.f;
-                DSC_HIP(hipEventElapsedTime(&ms, e0, e1));
-                ctx->free_events.push_back(e0);
-                ctx->free_events.push_back(e1);
-                mp.tune_ms[jx] = ms;
-                if (ms < best) { best = ms; mp.tuned_J = 1 << jx; }
-            }
-        }
-        int J = mp.tuned_J;
+    }
+    // 6b. FP64 dense tiles, merged per (operator class, padded targets)
+    std::map<std::pair<int, int>, std::vector<int>> groups;
+    for (int b : order) {
+        const Problem& P = PS[b];
+        if (P.pairs && P.plan->dense_ops && prm.precision == DISCOVER_FP64)
+            groups[{P.plan->dense_cls, P.TP}].push_back(b);
+    }
+    int gi = 0;
+    for (auto& g : groups) {
+        const int cls = g.first.first, TP = g.first.second;
+        const std::vector<int>& mem = g.second;
+        int J = 1;
         if (prm.tile_j > 0) {
-            // caller-forced width, rounded down to a power of two built for this TP
-            J = 1;
-            while (J * 2 <= std::min(prm.tile_j, max_J(P.TP))) J *= 2;
+            while (J * 2 <= std::min(prm.tile_j, max_J(TP))) J *= 2;
+        } else {
+            std::string key = "dense";
+            for (int b : mem) {
+                key += PS[b].plan->key;
+                key.append((const char*)&PS[b].n, sizeof(int));
+            }
+            J = tune_dense(ctx, key, cls, TP, dpa, PS, mem, st);
         }
-        P.tile_j = J;
         const int jx = J == 4 ? 2 : J == 2 ? 1 : 0;
-        a.tiles = mp.dtilesJ[jx];
-        a.n_tiles = mp.n_dtilesJ[jx];
+        std::vector<int4> tiles;
+        for (int b : mem) {
+            PS[b].tile_j = J;
+            for (const int2& t : PS[b].plan->dtilesJ[jx]) tiles.push_back(make_int4(b, t.x, t.y, 0));
+        }
+        const int4* dt = ctx->upload("scr_dtiles" + std::to_string(gi++), tiles, st);
         KTimer kt(ctx, st, "screen_pairs");
-        launch_pairs(pl.dense_cls, a, false, P.TP, J, st);
+        launch_pairs(cls, dpa, dt, (int64_t)tiles.size(), false, TP, J, st);
         check_launch("k_screen_pairs");
     }
-    if (pl.list_ops && pl.n_ltiles) {
-        a.tiles = pl.ltiles; a.ilist = pl.ilist; a.icount = pl.icount;
-        a.n_tiles = pl.n_ltiles; a.opmask = pl.list_ops;
-        KTimer kt(ctx, st, "screen_pairs_list");
-        launch_pairs(3, a, true, P.TP, 1, st);
-        check_launch("k_screen_pairs(list)");
+    // 6c. same-unit add/sub partner lists (FP64 in every form), merged per TP
+    std::map<int, std::vector<int4>> lgroups;
+    for (int b : order) {
+        const Problem& P = PS[b];
+        if (!P.pairs || !P.plan->list_ops) continue;
+        for (const int4& t : P.plan->ltiles) lgroups[P.TP].push_back(make_int4(b, t.x, t.y, t.z));
     }
-    const EvalCtx ev = P.ev();
+    if (!lgroups.empty()) {
+        // list-mode arguments differ from the dense ones only in the operator mask
+        std::vector<PairArgs> pl2 = pa;
+        for (int b = 0; b < nb; b++) pl2[b].opmask = PS[b].plan->list_ops;
+        const ctab<PairArgs> dpl = ct(ctx->upload("scr_pairs_list", pl2, st));
+        int li = 0;
+        for (auto& g : lgroups) {
+            const int4* dt = ctx->upload("scr_ltiles" + std::to_string(li++), g.second, st);
+            KTimer kt(ctx, st, "screen_pairs_list");
+            launch_pairs(3, dpl, dt, (int64_t)g.second.size(), true, g.first, 1, st);
+            check_launch("k_screen_pairs(list)");
+        }
+    }
+    // 7. exact decisions for the ill-conditioned candidates
+    std::vector<FixArgs> fa(nb);
+    for (int b = 0; b < nb; b++) {
+        const Problem& P = PS[b];
+        FixArgs& a = fa[b];
+        a = FixArgs{};
+        a.ids = P.fix_ids; a.cnt = P.ctr + 1; a.cap = P.fix_cap; a.ev = P.ev(); a.o = P.ops();
+        a.n = P.n; a.T = P.T; a.mode = prm.score_mode; a.Yc = P.Yc; a.syy = P.syy; a.N = P.N;
+        a.scores = P.scores; a.nscored = P.ctr + 2; a.r2v = P.r2v; a.r2m = P.r2m; a.r2q = P.r2q;
+    }
     {
-        // exact decision for the ill-conditioned ones (persistent waves over
-        // the device-side count)
         KTimer kt(ctx, st, "screen_fixup");
-        k_fixup<DISCOVER_MAX_TARGETS><<<1024, 256, 0, st>>>(
-            a.fix_ids, a.fix_cnt, a.fix_cap, ev, ops, n, pb.T, prm.score_mode, P.Yc, P.syy, N,
-            P.scores, P.nscored, P.r2v, P.r2m, P.r2q);
+        const unsigned fb = (unsigned)std::max(1, std::min(1024, 4096 / nb));
+        k_fixup<<<dim3(fb, nb), 256, 0, st>>>(ct(ctx->upload("scr_fix", fa, st)));
         check_launch("k_fixup");
     }
-    if (!sp.stream3 || !pl.r3_ops || !pl.n_r3tiles) return;
-    // operator-limited rung 3 on top of the rung-2 operand statistics
-    unsigned long long* fix3 = ctr + 3;
-    R3Args g3{};
-    g3.tiles = pl.r3tiles; g3.klist = pl.ilist; g3.n_tiles = pl.n_r3tiles;
-    g3.n = n; g3.ldm = ldm; g3.ldn = ldn; g3.Mc = Mc;
-    g3.c1_lo = sp.rung_start[1]; g3.c1_hi = sp.rung_start[2];
-    g3.pe = sp.rung_start[sd.pool[3] + 1];
-    g3.B = sp.B;
-    g3.Vs = P.Vs; g3.Rs = P.Rs; g3.Cs = P.Cs; g3.Vf = P.Vf; g3.Rf = P.Rf; g3.Cf = P.Cf;
-    g3.mu = P.mu; g3.mur = P.mur; g3.valid = P.valid; g3.mat_raw = pl.mat_raw;
-    g3.mat_unit = pl.mat_unit; g3.r2v = P.r2v; g3.r2m = P.r2m; g3.r2q = P.r2q; g3.msq = P.msq;
-    g3.Yn = P.Yn; g3.ysum = P.ysum; g3.T = pb.T; g3.mode = prm.score_mode;
-    g3.opmask = pl.r3_ops; g3.sd = sd; g3.N = N; g3.scores = P.scores; g3.nscored = P.nscored;
-    g3.fix_cap = a.fix_cap;
-    g3.fix_ids = ctx->buf<int64_t>("fix_ids3", g3.fix_cap);
-    g3.fix_cnt = fix3;
-    {
-        KTimer kt(ctx, st, "screen_r3");
-        const unsigned blocks = (unsigned)cdiv(g3.n_tiles, 4);
-        switch (P.TP) {
-        case 1: k_screen_r3<31, 2, 1><<<blocks, 256, 0, st>>>(g3); break;
-        case 2: k_screen_r3<31, 2, 2><<<blocks, 256, 0, st>>>(g3); break;
-        case 4: k_screen_r3<31, 1, 4><<<blocks, 256, 0, st>>>(g3); break;
-        case 8: k_screen_r3<31, 1, 8><<<blocks, 256, 0, st>>>(g3); break;
-        default: k_screen_r3<31, 1, 16><<<blocks, 256, 0, st>>>(g3); break;
+    // 8. operator-limited rung 3 on top of the rung-2 operand statistics
+    std::vector<FixArgs> fa3;
+    for (int b = 0; b < nb; b++) {
+        Problem& P = PS[b];
+        const Plan& pl = *P.plan;
+        const Space& sp = pl.sp;
+        const SpaceDev& sd = sp.d;
+        if (!sp.stream3 || !pl.r3_ops || !pl.n_r3tiles) continue;
+        R3Args g3{};
+        g3.tiles = pl.r3tiles; g3.klist = pl.ilist; g3.n_tiles = pl.n_r3tiles;
+        g3.n = P.n; g3.ldm = P.ldm; g3.ldn = P.ldn; g3.Mc = P.Mc;
+        g3.c1_lo = sp.rung_start[1]; g3.c1_hi = sp.rung_start[2];
+        g3.pe = sp.rung_start[sd.pool[3] + 1];
+        g3.B = sp.B;
+        g3.Vs = P.Vs; g3.Rs = P.Rs; g3.Cs = P.Cs; g3.Vf = P.Vf; g3.Rf = P.Rf; g3.Cf = P.Cf;
+        g3.mu = P.mu; g3.mur = P.mur; g3.valid = P.valid; g3.mat_raw = pl.mat_raw;
+        g3.mat_unit = pl.mat_unit; g3.r2v = P.r2v; g3.r2m = P.r2m; g3.r2q = P.r2q; g3.msq = P.msq;
+        g3.Yn = P.Yn; g3.ysum = P.ysum; g3.T = P.T; g3.mode = prm.score_mode;
+        g3.opmask = pl.r3_ops; g3.sd = sd; g3.N = P.N; g3.scores = P.scores; g3.nscored = P.ctr + 2;
+        g3.fix_cap = P.fix_cap; g3.fix_ids = P.fix_ids3; g3.fix_cnt = P.ctr + 3;
+        {
+            KTimer kt(ctx, st, "screen_r3");
+            const unsigned blocks = (unsigned)cdiv(g3.n_tiles, 4);
+            switch (P.TP) {
+            case 1: k_screen_r3<31, 2, 1><<<blocks, 256, 0, st>>>(g3); break;
+            case 2: k_screen_r3<31, 2, 2><<<blocks, 256, 0, st>>>(g3); break;
+            case 4: k_screen_r3<31, 1, 4><<<blocks, 256, 0, st>>>(g3); break;
+            case 8: k_screen_r3<31, 1, 8><<<blocks, 256, 0, st>>>(g3); break;
+            default: k_screen_r3<31, 1, 16><<<blocks, 256, 0, st>>>(g3); break;
+            }
+            check_launch("k_screen_r3");
         }
-        check_launch("k_screen_r3");
+        FixArgs a = fa[b];
+        a.ids = P.fix_ids3; a.cnt = P.ctr + 3; a.r2v = nullptr; a.r2m = nullptr; a.r2q = nullptr;
+        fa3.push_back(a);
     }
-    {
+    if (!fa3.empty()) {
         KTimer kt(ctx, st, "screen_fixup");
-        k_fixup<DISCOVER_MAX_TARGETS><<<1024, 256, 0, st>>>(
-            g3.fix_ids, g3.fix_cnt, g3.fix_cap, ev, ops, n, pb.T, prm.score_mode, P.Yc, P.syy, N,
-            P.scores, P.nscored, nullptr, nullptr, nullptr);
+        k_fixup<<<dim3(1024, (unsigned)fa3.size()), 256, 0, st>>>(ct(ctx->upload("scr_fix3", fa3, st)));
         check_launch("k_fixup");
     }
 }
 
-// Exact top-k of list t (pool, rescore, sort, duplicate groups).  The
-// pool holds every candidate whose score can reach the K-th largest
-// approximate score minus the error margin; it is rescored exactly and
-// grouped in (-score, ID) order.  If the pool does not reach below the
-// near-tie window of the k-th group, K grows and the selection repeats.
-static void select_list(discover_ctx* ctx, const discover_problem& pb,
-                        const discover_screen_params& prm, Problem& P, int t, double margin,
-                        int64_t* out_ids, double* out_sc, discover_screen_stats& stats,
-                        hipStream_t st) {
-    const Plan& pl = *P.plan;
-    const Space& sp = pl.sp;
-    const int64_t N = sp.n_raw();
-    const double* sc = P.scores + (int64_t)t * N;
+// Launch one round of exact top-k for the given lists.  The pool of a list
+// holds every candidate whose score can reach its K-th largest approximate
+// score minus the error margin; it is rescored exactly and grouped in
+// (-score, ID) order.
+static void select_round(discover_ctx* ctx, const discover_problem* probs,
+                         const discover_screen_params& prm, std::vector<Problem>& PS,
+                         const std::vector<ListState>& LS, const std::vector<int>& act,
+                         const std::vector<double>& margin, int64_t* out_ids, double* out_sc,
+                         const std::vector<int64_t>& row, hipStream_t st,
+                         std::vector<SelArgs>& sa) {
+    const int nl = (int)act.size();
     const int k = prm.k;
-    int64_t K = 2 * (int64_t)k + pb.n_exclude + 64;
-    uint32_t* hist = ctx->buf<uint32_t>("hist", 4096);
-    uint32_t* sel = ctx->buf<uint32_t>("sel", 4);
-    int64_t* stv = ctx->buf<int64_t>("selst", 2);
-    unsigned long long* cnt = ctx->buf<unsigned long long>("poolcnt", 1);
-    int64_t* res = ctx->buf<int64_t>("groupres", 8);
-    unsigned long long* maxerr = ctx->buf<unsigned long long>("maxerr", 1);
-    DSC_HIP(hipMemsetAsync(maxerr, 0, 8, st));
-    Ops ops{P.Vf, P.Rf, P.ldn};
-    int64_t cap = 4 * K + 4096;
-    int64_t fcap = 64 * cap;
-    for (;;) {
-        {
-            KTimer kt(ctx, st, "select");
-            radix_select(sc, N, K, hist, sel, stv, st);
-        }
-        int64_t* pool = ctx->buf<int64_t>("pool", cap);
-        double* ps = ctx->buf<double>("ps", cap);
-        uint8_t* pex = ctx->buf<uint8_t>("pex", cap);
-        int32_t* order = ctx->buf<int32_t>("order", cap);
-        int32_t* lo = ctx->buf<int32_t>("wlo", cap);
-        int32_t* wc = ctx->buf<int32_t>("wcnt", cap);
-        int64_t* off = ctx->buf<int64_t>("woff", cap + 1);
-        uint8_t* flag = ctx->buf<uint8_t>("dupflag", fcap);
-        int32_t* parent = ctx->buf<int32_t>("gparent", cap + 1);
-        int32_t* blk = ctx->buf<int32_t>("gblk", cap + 1);
-        unsigned long long* repid = ctx->buf<unsigned long long>("grepid", cap + 1);
-        int32_t* reppos = ctx->buf<int32_t>("greppos", cap + 1);
-        int32_t* headpos = ctx->buf<int32_t>("gheadpos", (size_t)k + 1);
-        DSC_HIP(hipMemsetAsync(cnt, 0, 8, st));
-        const unsigned hb = (unsigned)std::min<int64_t>(1024, std::max<int64_t>(1, cdiv(N, 256 * 8)));
-        k_compact<<<hb, 256, 0, st>>>(sc, N, sel, stv, margin, cap, pool, cnt);
-        check_launch("k_compact");
-        {
-            KTimer kt(ctx, st, "rescore");
-            k_rescore<DISCOVER_MAX_TARGETS><<<(unsigned)std::min<int64_t>(2048, cdiv(cap, 4)), 256, 0, st>>>(
-                pool, cnt, cap, P.ev(), ops, P.n, P.T, prm.score_mode, t,
-                P.Yc, P.syy, pb.exclude, pb.exclude ? pb.n_exclude : 0, ps, pex, sc, maxerr);
-            check_launch("k_rescore");
-        }
-        {
-            KTimer kt(ctx, st, "sort_dedup");
-            k_bitonic<<<1, 1024, 0, st>>>(ps, pool, cnt, cap, order);
-            k_rank<<<(unsigned)cdiv(cap, 256), 256, 0, st>>>(ps, pool, cnt, cap, order);
-            k_window<<<(unsigned)std::min<int64_t>(1024, cdiv(cap, 256)), 256, 0, st>>>(ps, order, cnt, cap, lo, wc);
-            k_scan_offsets<<<1, 1024, 0, st>>>(wc, cnt, cap, off);
-            check_launch("k_sort");
-        }
-        if (prm.dedup) {
-            KTimer kt(ctx, st, "dedup_pairs");
-            k_pairs<<<2048, 256, 0, st>>>(pool, order, lo, off, cnt, cap, P.ev(), ops, P.n, flag, fcap);
-            check_launch("k_pairs");
-        }
-        {
-            KTimer kt(ctx, st, "groups");
-            k_groups<<<1, GRP_THREADS, 0, st>>>(pool, ps, pex, order, lo, off, flag, cnt, cap, fcap, k,
-                                                prm.dedup, sel, stv, margin, parent, blk, repid,
-                                                reppos, headpos, out_ids, out_sc, res);
-            check_launch("k_groups");
-        }
-        int64_t h_res[8];
-        int h_bad = 0;
-        double h_err = 0.0;
-        DSC_HIP(hipMemcpyAsync(h_res, res, sizeof h_res, hipMemcpyDeviceToHost, st));
-        DSC_HIP(hipMemcpyAsync(&h_err, maxerr, 8, hipMemcpyDeviceToHost, st));
-        DSC_HIP(hipMemcpyAsync(&h_bad, P.bad, sizeof h_bad, hipMemcpyDeviceToHost, st));
-        DSC_HIP(hipStreamSynchronize(st));
-        if (h_bad) DSC_FAIL(DISCOVER_E_NUMERIC, "a target column is constant or not finite");
-        if (h_res[4] > cap) {                       // pool overflow: enlarge and redo
-            cap = h_res[4] + 1024;
-            fcap = std::max(fcap, 64 * cap);
-            stats.pool_rounds += 1;
-            continue;
-        }
-        if (prm.dedup && h_res[3] > fcap) {         // pair-flag overflow
-            fcap = h_res[3] + 1024;
-            stats.pool_rounds += 1;
-            continue;
-        }
-        stats.pool_size += h_res[4];
-        stats.max_lowprec_err = std::max(stats.max_lowprec_err, h_err);
-        if (h_res[1] || K >= N) {
-            stats.n_selected += h_res[0];
-            stats.n_merged += h_res[2];
-            return;
-        }
-        stats.pool_rounds += 1;
-        K = std::min<int64_t>(N, K * 4);
-        cap = 4 * K + 4096;
-        fcap = std::max(fcap, 64 * cap);
+    Arena ar;
+    std::vector<std::vector<size_t>> o(nl);
+    for (int q = 0; q < nl; q++) {
+        const ListState& L = LS[act[q]];
+        const size_t cap = (size_t)L.cap, fcap = (size_t)L.fcap;
+        auto& v = o[q];
+        v.push_back(ar.add(cap * 8));              // pool
+        v.push_back(ar.add(cap * 8));              // ps
+        v.push_back(ar.add(cap));                  // pex
+        v.push_back(ar.add(cap * 4));              // order
+        v.push_back(ar.add(cap * 4));              // lo
+        v.push_back(ar.add(cap * 4));              // wc
+        v.push_back(ar.add((cap + 1) * 8));        // off
+        v.push_back(ar.add(fcap));                 // flag
+        v.push_back(ar.add((cap + 1) * 4));        // parent
+        v.push_back(ar.add((cap + 1) * 4));        // blk
+        v.push_back(ar.add((cap + 1) * 8));        // repid
+        v.push_back(ar.add((cap + 1) * 4));        // reppos
+        v.push_back(ar.add(((size_t)k + 1) * 4));  // headpos
+        v.push_back(ar.add(64));                   // res
+        v.push_back(ar.add(64));                   // cnt, maxerr, st[2], sel[4]
+        v.push_back(ar.add(4096 * 4));             // hist
+    }
+    char* base = (char*)ctx->raw("sel_arena", ar.total);
+    sa.assign(nl, SelArgs{});
+    std::vector<RadixArgs> ra(nl);
+    std::vector<FillSeg> fills;
+    int64_t Nmax = 1, capmax = 1;
+    for (int q = 0; q < nl; q++) {
+        const ListState& L = LS[act[q]];
+        const Problem& P = PS[L.b];
+        const discover_problem& pb = probs[L.b];
+        const auto& v = o[q];
+        SelArgs& a = sa[q];
+        int j = 0;
+        auto at = [&](void) { return base + v[j++]; };
+        a.pool = (int64_t*)at(); a.ps = (double*)at(); a.pex = (uint8_t*)at();
+        a.order = (int32_t*)at(); a.lo = (int32_t*)at(); a.wc = (int32_t*)at();
+        a.off = (int64_t*)at(); a.flag = (uint8_t*)at();
+        a.parent = (int32_t*)at(); a.blk = (int32_t*)at(); a.repid = (unsigned long long*)at();
+        a.reppos = (int32_t*)at(); a.headpos = (int32_t*)at(); a.res = (int64_t*)at();
+        char* misc = at();
+        uint32_t* hist = (uint32_t*)at();
+        a.cnt = (unsigned long long*)misc;
+        a.maxerr = (unsigned long long*)(misc + 8);
+        int64_t* stv = (int64_t*)(misc + 16);
+        uint32_t* sel = (uint32_t*)(misc + 32);
+        a.sel = sel; a.st = stv;
+        a.sc = P.scores + (int64_t)L.t * P.N; a.N = P.N;
+        a.margin = margin[L.b]; a.cap = L.cap; a.fcap = L.fcap;
+        a.ev = P.ev(); a.o = P.ops(); a.n = P.n; a.T = P.T; a.mode = prm.score_mode; a.t = L.t;
+        a.k = k; a.dedup = prm.dedup;
+        a.Yc = P.Yc; a.syy = P.syy;
+        a.excl = pb.exclude; a.n_excl = pb.exclude ? pb.n_exclude : 0;
+        a.out_ids = out_ids + (row[L.b] + L.t) * k;
+        a.out_sc = out_sc + (row[L.b] + L.t) * k;
+        ra[q] = RadixArgs{a.sc, P.N, L.K, hist, sel, stv};
+        fills.push_back(fill_seg(misc, 16, 0u));            // pool count, maximum error
+        Nmax = std::max(Nmax, P.N);
+        capmax = std::max(capmax, L.cap);
+    }
+    fill_all(ctx, "sel_fills", fills, st);
+    const ctab<SelArgs> dsa = ct(ctx->upload("sel_args", sa, st));
+    const RadixArgs* dra = ctx->upload("sel_radix", ra, st);
+    {
+        KTimer kt(ctx, st, "select");
+        radix_select(dra, nl, Nmax, st);
+    }
+    const unsigned hb = (unsigned)std::min<int64_t>(1024, std::max<int64_t>(1, cdiv(Nmax, 256 * 8)));
+    k_compact<<<dim3(hb, nl), 256, 0, st>>>(dsa);
+    check_launch("k_compact");
+    {
+        KTimer kt(ctx, st, "rescore");
+        k_rescore<<<dim3((unsigned)std::min<int64_t>(std::max(64, 2048 / nl), cdiv(capmax, 4)), nl), 256, 0, st>>>(dsa);
+        check_launch("k_rescore");
+    }
+    {
+        KTimer kt(ctx, st, "sort_dedup");
+        k_bitonic<<<nl, 1024, 0, st>>>(dsa);
+        k_rank<<<dim3((unsigned)cdiv(capmax, 256), nl), 256, 0, st>>>(dsa);
+        k_window<<<dim3((unsigned)std::min<int64_t>(1024, cdiv(capmax, 256)), nl), 256, 0, st>>>(dsa);
+        k_scan_offsets<<<nl, 1024, 0, st>>>(dsa);
+        check_launch("k_sort");
+    }
+    if (prm.dedup) {
+        KTimer kt(ctx, st, "dedup_pairs");
+        k_pairs<<<dim3((unsigned)std::max(64, 2048 / nl), nl), 256, 0, st>>>(dsa);
+        check_launch("k_pairs");
+    }
+    {
+        KTimer kt(ctx, st, "groups");
+        k_groups<<<nl, GRP_THREADS, 0, st>>>(dsa);
+        check_launch("k_groups");
     }
 }
 
@@ -2120,6 +2488,7 @@ static void validate(const discover_problem* probs, int32_t nb, const discover_s
                      const int64_t* out_ids, const double* out_sc, const double* out_values,
                      int64_t ldv) {
     DSC_REQUIRE(probs && prm && nb >= 1, "probs/prm must be non-NULL and n_problems >= 1");
+    DSC_REQUIRE(nb <= 65535, "n_problems = %d > 65535", nb);
     DSC_REQUIRE(out_ids && out_sc, "out_ids and out_scores are required");
     DSC_REQUIRE(prm->rung >= 0 && prm->rung <= DISCOVER_MAX_RUNG, "rung %d outside 0..3", prm->rung);
     DSC_REQUIRE(prm->k >= 1, "k must be >= 1");
@@ -2147,11 +2516,163 @@ static void validate(const discover_problem* probs, int32_t nb, const discover_s
     }
 }
 
+// Capacities of every list of a call, remembered so that a captured run of
+// the same call starts from the sizes the eager run settled on.
+struct SelMemo {
+    std::vector<int64_t> K, cap, fcap;
+};
+
+static std::string call_key(const discover_problem* probs, int nb, const discover_screen_params& prm) {
+    std::string k((const char*)&prm, sizeof prm);
+    for (int b = 0; b < nb; b++) {
+        const discover_problem& p = probs[b];
+        const int64_t f[8] = {p.n, p.p, p.T, p.B, (int64_t)(intptr_t)p.X, (int64_t)(intptr_t)p.Y,
+                              (int64_t)(intptr_t)p.exclude, p.n_exclude};
+        k.append((const char*)f, sizeof f);
+        if (p.B && p.units) k.append((const char*)p.units, sizeof(int32_t) * p.p * p.B);
+    }
+    return k;
+}
+
+static void generate_screen(discover_ctx* ctx, const discover_problem* probs, int nb,
+                            const discover_screen_params& prm, int64_t* out_ids, double* out_sc,
+                            double* out_values, int64_t ldv, discover_screen_stats* out_stats,
+                            hipStream_t st) {
+    std::vector<Problem> PS;
+    screen_all(ctx, probs, nb, prm, PS, st);
+    std::vector<discover_screen_stats> stats(nb);
+    std::vector<double> margin(nb);
+    std::vector<int64_t> row(nb);
+    std::vector<ListState> LS;
+    int64_t r0 = 0;
+    for (int b = 0; b < nb; b++) {
+        const Problem& P = PS[b];
+        discover_screen_stats& s = stats[b];
+        s = discover_screen_stats{};
+        s.n_raw = P.N;
+        s.n_unit_valid = P.plan->sp.n_unit_valid;
+        s.tile_j = P.tile_j;
+        margin[b] = 4.0 * P.n * EPS64 * KAPPA_MAX;
+        if (prm.precision != DISCOVER_FP64) {
+            s.guard_band = lowprec_delta(prm.precision, P.n);
+            margin[b] = std::max(margin[b], s.guard_band);
+        }
+        row[b] = r0;
+        r0 += P.Tl;
+        for (int t = 0; t < P.Tl; t++) {
+            ListState L;
+            L.b = b; L.t = t;
+            L.K = 2 * (int64_t)prm.k + probs[b].n_exclude + 64;
+            L.cap = 4 * L.K + 4096;
+            L.fcap = 64 * L.cap;
+            LS.push_back(L);
+        }
+    }
+    const std::string ck = call_key(probs, nb, prm);
+    auto mit = ctx->batches.find("sel" + ck);
+    if (mit != ctx->batches.end()) {            // start from the sizes a previous call settled on
+        const SelMemo& m = *std::static_pointer_cast<SelMemo>(mit->second);
+        if (m.K.size() == LS.size())
+            for (size_t l = 0; l < LS.size(); l++) { LS[l].K = m.K[l]; LS[l].cap = m.cap[l]; LS[l].fcap = m.fcap[l]; }
+    }
+    std::vector<int> act(LS.size());
+    for (size_t l = 0; l < LS.size(); l++) act[l] = (int)l;
+    std::vector<SelArgs> sa;
+    bool checked_bad = false;
+    while (!act.empty()) {
+        select_round(ctx, probs, prm, PS, LS, act, margin, out_ids, out_sc, row, st, sa);
+        if (ctx->capturing) break;              // results are checked after the replay
+        // one synchronisation per round: outcome of every active list
+        const int nl = (int)act.size();
+        std::vector<int64_t> h_res(8 * (size_t)nl);
+        std::vector<unsigned long long> h_err(nl);
+        for (int q = 0; q < nl; q++) {
+            DSC_HIP(hipMemcpyAsync(&h_res[8 * q], sa[q].res, 64, hipMemcpyDeviceToHost, st));
+            DSC_HIP(hipMemcpyAsync(&h_err[q], sa[q].maxerr, 8, hipMemcpyDeviceToHost, st));
+        }
+        std::vector<unsigned long long> h_ctr(4 * (size_t)nb);
+        if (!checked_bad)
+            for (int b = 0; b < nb; b++)
+                DSC_HIP(hipMemcpyAsync(&h_ctr[4 * b], PS[b].ctr, 32, hipMemcpyDeviceToHost, st));
+        DSC_HIP(hipStreamSynchronize(st));
+        if (!checked_bad) {
+            for (int b = 0; b < nb; b++) {
+                if ((int)(h_ctr[4 * b] & 0xFFFFFFFFull))
+                    DSC_FAIL(DISCOVER_E_NUMERIC, "problem %d: a target column is constant or not finite", b);
+                stats[b].n_scored = (int64_t)h_ctr[4 * b + 2];
+            }
+            checked_bad = true;
+        }
+        std::vector<int> next;
+        for (int q = 0; q < nl; q++) {
+            ListState& L = LS[act[q]];
+            discover_screen_stats& s = stats[L.b];
+            const int64_t* r = &h_res[8 * q];
+            const int64_t N = PS[L.b].N;
+            if (r[4] > L.cap) {                       // pool overflow: enlarge and redo
+                L.cap = r[4] + 1024;
+                L.fcap = std::max(L.fcap, 64 * L.cap);
+                s.pool_rounds += 1;
+                next.push_back(act[q]);
+                continue;
+            }
+            if (prm.dedup && r[3] > L.fcap) {         // pair-flag overflow
+                L.fcap = r[3] + 1024;
+                s.pool_rounds += 1;
+                next.push_back(act[q]);
+                continue;
+            }
+            s.pool_size += r[4];
+            double e;
+            std::memcpy(&e, &h_err[q], 8);
+            s.max_lowprec_err = std::max(s.max_lowprec_err, e);
+            if (r[1] || L.K >= N) {
+                s.n_selected += r[0];
+                s.n_merged += r[2];
+                L.done = true;
+                continue;
+            }
+            s.pool_rounds += 1;
+            L.K = std::min<int64_t>(N, L.K * 4);
+            L.cap = 4 * L.K + 4096;
+            L.fcap = std::max(L.fcap, 64 * L.cap);
+            next.push_back(act[q]);
+        }
+        act.swap(next);
+    }
+    if (!ctx->capturing) {
+        auto m = std::make_shared<SelMemo>();
+        for (const ListState& L : LS) { m->K.push_back(L.K); m->cap.push_back(L.cap); m->fcap.push_back(L.fcap); }
+        if (ctx->batches.size() >= 256) ctx->batches.clear();
+        ctx->batches["sel" + ck] = m;
+    }
+    if (out_values) {
+        std::vector<ValArgs> va;
+        int64_t mmax = 0;
+        for (int b = 0; b < nb; b++) {
+            const Problem& P = PS[b];
+            ValArgs a{};
+            a.ids = out_ids + row[b] * prm.k; a.m = (int64_t)P.Tl * prm.k; a.ev = P.ev(); a.o = P.ops();
+            a.n = P.n; a.out = out_values + row[b] * prm.k * ldv; a.ldv = ldv;
+            va.push_back(a);
+            mmax = std::max(mmax, a.m);
+        }
+        KTimer kt(ctx, st, "values");
+        k_values<<<dim3((unsigned)cdiv(mmax, 4), nb), 256, 0, st>>>(ct(ctx->upload("scr_values", va, st)));
+        check_launch("k_values");
+    }
+    if (!ctx->capturing) {
+        DSC_HIP(hipStreamSynchronize(st));
+        ctx->resolve_timing();
+        if (out_stats)
+            for (int b = 0; b < nb; b++) out_stats[b] = stats[b];
+    }
+}
+
 }  // namespace dsc
 
 extern "C" discover_status discover_generate_screen(discover_ctx* ctx, const discover_problem* probs,
-                                                    int32_t n_problems,
-                                                    const discover_screen_params* prm,
+                                                    int32_t n_problems, const discover_screen_params* prm,
                                                     int64_t* out_ids, double* out_scores,
                                                     double* out_values, int64_t ldv,
                                                     discover_screen_stats* out_stats, void* stream) {
@@ -2160,39 +2681,7 @@ extern "C" discover_status discover_generate_screen(discover_ctx* ctx, const dis
         DSC_REQUIRE(ctx, "ctx is NULL");
         validate(probs, n_problems, prm, out_ids, out_scores, out_values, ldv);
         DSC_HIP(hipSetDevice(ctx->device));
-        hipStream_t st = (hipStream_t)stream;
-        int64_t row = 0;
-        for (int b = 0; b < n_problems; b++) {
-            const discover_problem& pb = probs[b];
-            Problem P{};
-            discover_screen_stats stats{};
-            screen_problem(ctx, pb, *prm, P, st);
-            stats.n_raw = P.plan->sp.n_raw();
-            stats.n_unit_valid = P.plan->sp.n_unit_valid;
-            stats.tile_j = P.tile_j;
-            double margin = 4.0 * P.n * EPS64 * KAPPA_MAX;
-            if (prm->precision != DISCOVER_FP64) {
-                stats.guard_band = lowprec_delta(prm->precision, P.n);
-                margin = std::max(margin, stats.guard_band);
-            }
-            const int Tl = P.Tl;
-            for (int t = 0; t < Tl; t++) {
-                select_list(ctx, pb, *prm, P, t, margin, out_ids + (row + t) * prm->k,
-                            out_scores + (row + t) * prm->k, stats, st);
-            }
-            if (out_values) {
-                KTimer kt(ctx, st, "values");
-                Ops ops{P.Vf, P.Rf, P.ldn};
-                const int64_t m = (int64_t)Tl * prm->k;
-                k_values<<<(unsigned)cdiv(m, 4), 256, 0, st>>>(out_ids + row * prm->k, m, P.ev(), ops, P.n,
-                                                               out_values + row * prm->k * ldv, ldv);
-                check_launch("k_values");
-            }
-            stats.n_scored = (int64_t)download1(P.nscored, st);
-            DSC_HIP(hipStreamSynchronize(st));
-            ctx->resolve_timing();
-            if (out_stats) out_stats[b] = stats;
-            row += Tl;
-        }
+        generate_screen(ctx, probs, n_problems, *prm, out_ids, out_scores, out_values, ldv, out_stats,
+                        (hipStream_t)stream);
     });
 }

@@ -18,15 +18,42 @@ static __device__ __forceinline__ uint64_t fx_key(double x) {
     return (uint64_t)(c * 4503599627370496.0);          // * 2^52
 }
 
-static __global__ __launch_bounds__(256) void k_hist(const double* __restrict__ sc, int64_t N,
-                                                     int level, const uint32_t* __restrict__ sel,
-                                                     uint32_t* __restrict__ hist) {
+// One radix selection per list: x[0..N) holds the values (entries <= 0 are
+// ignored), K the rank wanted; hist is a 4096-bin scratch histogram, sel
+// the three selected 12-bit digits, st[0] the remaining rank and st[1] the
+// take-all flag (fewer than K positive entries).
+struct RadixArgs {
+    const double* x;
+    int64_t N;
+    int64_t K;
+    uint32_t* hist;
+    uint32_t* sel;
+    int64_t* st;
+};
+
+static __global__ __launch_bounds__(256) void k_radix_init(ctab<RadixArgs> A) {
+    const RadixArgs& a = tab(A, blockIdx.x);
+    DSC_GLOBAL(a.hist); DSC_GLOBAL(a.sel); DSC_GLOBAL(a.st);
+    for (int b = threadIdx.x; b < 4096; b += 256) a.hist[b] = 0;
+    if (threadIdx.x < 4) a.sel[threadIdx.x] = 0;
+    if (threadIdx.x == 0) {
+        a.st[0] = a.K;
+        a.st[1] = 0;
+    }
+}
+
+// grid (blocks, lists)
+static __global__ __launch_bounds__(256) void k_hist(ctab<RadixArgs> A, int level) {
+    const RadixArgs& a = tab(A, blockIdx.y);
+    DSC_GLOBAL(a.x); DSC_GLOBAL(a.hist); DSC_GLOBAL(a.sel);
     __shared__ uint32_t h[4096];
     for (int b = threadIdx.x; b < 4096; b += 256) h[b] = 0;
     __syncthreads();
     uint32_t p0 = 0, p1 = 0;
-    if (level > 0) p0 = sel[0];
-    if (level > 1) p1 = sel[1];
+    if (level > 0) p0 = a.sel[0];
+    if (level > 1) p1 = a.sel[1];
+    const double* __restrict__ sc = a.x;
+    const int64_t N = a.N;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256) {
         const double x = sc[i];
         if (!(x > 0.0)) continue;
@@ -37,15 +64,18 @@ static __global__ __launch_bounds__(256) void k_hist(const double* __restrict__ 
     }
     __syncthreads();
     for (int b = threadIdx.x; b < 4096; b += 256)
-        if (h[b]) atomicAdd(&hist[b], h[b]);
+        if (h[b]) atomicAdd(&a.hist[b], h[b]);
 }
 
-// st[0] = remaining rank K, st[1] = take-all flag.  One block of 256
-// threads: thread t owns bins [16t, 16t+16); a suffix scan over threads
-// gives the count above each range.
-static __global__ __launch_bounds__(256) void k_find(const uint32_t* __restrict__ hist, int level,
-                                                     uint32_t* __restrict__ sel,
-                                                     int64_t* __restrict__ st) {
+// One block of 256 threads per list: thread t owns bins [16t, 16t+16); a
+// suffix scan over threads gives the count above each range.  The
+// histogram is cleared for the next level after it has been read.
+static __global__ __launch_bounds__(256) void k_find(ctab<RadixArgs> A, int level) {
+    const RadixArgs& a = tab(A, blockIdx.x);
+    DSC_GLOBAL(a.hist); DSC_GLOBAL(a.sel); DSC_GLOBAL(a.st);
+    uint32_t* __restrict__ hist = a.hist;
+    uint32_t* __restrict__ sel = a.sel;
+    int64_t* __restrict__ st = a.st;
     __shared__ int64_t part[256];
     const int t = threadIdx.x;
     int64_t loc = 0;
@@ -54,6 +84,7 @@ static __global__ __launch_bounds__(256) void k_find(const uint32_t* __restrict_
         hb[q] = hist[t * 16 + q];
         loc += hb[q];
     }
+    for (int q = 0; q < 16; q++) hist[t * 16 + q] = 0;
     part[t] = loc;
     __syncthreads();
     // inclusive suffix sums (Hillis-Steele over 256 entries)
@@ -94,24 +125,16 @@ static __device__ __forceinline__ double select_threshold(const uint32_t* sel, c
     return (double)key * 2.220446049250313e-16;          // * 2^-52 (exact)
 }
 
-static inline double host_threshold(const uint32_t* sel, const int64_t* st) {
-    if (st[1]) return 0.0;
-    const uint64_t key = ((uint64_t)sel[0] << 40) | ((uint64_t)sel[1] << 28) | ((uint64_t)sel[2] << 16);
-    return (double)key * 2.220446049250313e-16;
-}
-
-// Launch the three levels; afterwards sel/st describe the K-th largest
-// positive entry of x (st[1] = 1 when fewer than K positive entries exist).
-static inline void radix_select(const double* x, int64_t N, int64_t K, uint32_t* hist,
-                                uint32_t* sel, int64_t* st, hipStream_t s) {
-    const int64_t init[2] = {K, 0};
-    DSC_HIP(hipMemcpyAsync(st, init, sizeof init, hipMemcpyHostToDevice, s));
-    DSC_HIP(hipMemsetAsync(sel, 0, 16, s));
-    const unsigned hb = (unsigned)std::min<int64_t>(1024, std::max<int64_t>(1, cdiv(N, 256 * 8)));
+// Launch the selections of nl lists (device table A); afterwards each
+// list's sel/st describe its K-th largest positive entry.
+static inline void radix_select(const RadixArgs* Ad, int nl, int64_t Nmax, hipStream_t s) {
+    if (nl <= 0) return;
+    const ctab<RadixArgs> A = ct(Ad);
+    const unsigned hb = (unsigned)std::min<int64_t>(1024, std::max<int64_t>(1, cdiv(Nmax, 256 * 8)));
+    k_radix_init<<<nl, 256, 0, s>>>(A);
     for (int level = 0; level < 3; level++) {
-        DSC_HIP(hipMemsetAsync(hist, 0, 4096 * 4, s));
-        k_hist<<<hb, 256, 0, s>>>(x, N, level, sel, hist);
-        k_find<<<1, 256, 0, s>>>(hist, level, sel, st);
+        k_hist<<<dim3(hb, nl), 256, 0, s>>>(A, level);
+        k_find<<<nl, 256, 0, s>>>(A, level);
     }
     check_launch("radix_select");
 }
