@@ -236,6 +236,39 @@ discover_status discover_omp(discover_ctx* ctx, const discover_l0_problem* probs
                              int32_t* out_active, double* out_coef, double* out_rmse,
                              double* out_resid, int64_t ldr, void* stream);
 
+/* The SISSO loop (cited SISSO method, Summary; iterative generation ->
+ * screening -> sparsifying, Software Description) over a batch of datasets
+ * of uneven n and p, as one sequence of batched launches: for d = 1..D
+ * every dataset is screened (FP64 or the precision form of prm) against
+ * its target (d = 1) or the residuals of its m best (d-1)-models (MAX
+ * score when m > 1), the k selected features are appended to its
+ * subspace (earlier selections and their duplicate groups excluded), and
+ * exhaustive L0 (as discover_l0_fit) fits its target over all d-subsets.
+ * With use_graph = 1 the first call with a given set of inputs and outputs
+ * runs eagerly and then captures the sequence into a hipGraph; a later
+ * call with the same pointers and sizes replays the graph, checks on the
+ * device that every capacity held and every selection was complete, and
+ * runs eagerly instead if not.  The call returns with results ready.
+ *
+ *   probs        host [n_problems]; T = 1 (Y = the target), no exclude list
+ *   prm          score_mode DISCOVER_SCORE_PER_TARGET (the first dimension has one target)
+ *   D, m         1..3 dimensions; models per dimension 1..DISCOVER_MAX_TARGETS
+ *   out_ids      device int64 [n_problems][D][k]: the subspace rows in order
+ *   out_scores   device double [n_problems][D][k]
+ *   out_subsets  device int32 [n_problems][D][m][3] rows of the subspace (first d used, rest -1)
+ *   out_rmse     device double [n_problems][D][m]
+ *   out_coef     device double [n_problems][D][m][4] intercept first (first d+1 used, rest NaN)
+ *   out_replayed host int32, or NULL: 1 when a captured graph was replayed, 0 when
+ *                the call ran eagerly, -1 when it ran eagerly and capturing the graph
+ *                for later calls failed (discover_last_error says why)
+ * Errors: as discover_generate_screen and discover_l0_fit. */
+discover_status discover_sisso_batch(discover_ctx* ctx, const discover_problem* probs,
+                                     int32_t n_problems, const discover_screen_params* prm,
+                                     int32_t D, int32_t m, int32_t use_graph,
+                                     int64_t* out_ids, double* out_scores, int32_t* out_subsets,
+                                     double* out_rmse, double* out_coef, int32_t* out_replayed,
+                                     void* stream);
+
 /* Number of raw candidates |P_R| of a search space (host only). */
 int64_t discover_count(int32_t p, const discover_screen_params* prm);
 

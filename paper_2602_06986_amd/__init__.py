@@ -66,7 +66,8 @@ class L0Stats(C.Structure):
 # Every symbol include/discover.h declares.
 SYMBOLS = ("discover_create", "discover_destroy", "discover_last_error",
            "discover_generate_screen", "discover_l0_fit", "discover_omp", "discover_count",
-           "discover_decode", "discover_set_timing", "discover_timing", "discover_reset_timing")
+           "discover_decode", "discover_set_timing", "discover_timing", "discover_reset_timing",
+           "discover_sisso_batch")
 
 _lib = None
 
@@ -97,6 +98,9 @@ def lib():
         L.discover_set_timing.argtypes = [P, C.c_int32]
         L.discover_timing.argtypes = [P, C.c_char_p, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
         L.discover_reset_timing.argtypes = [P]
+        L.discover_sisso_batch.argtypes = [P, C.POINTER(Problem), C.c_int32, C.POINTER(ScreenParams),
+                                           C.c_int32, C.c_int32, C.c_int32, P, P, P, P, P,
+                                           C.POINTER(C.c_int32), P]
         _lib = L
     return _lib
 
@@ -372,6 +376,50 @@ class Context:
                                 "subsets": sub, "rmse": rmse, "coef": coef, "l0_stats": l0st})
             targets = [fits[b][3] for b in range(nb)]
         return [{"dims": dims[b], "S_ids": S_ids[b], "F": F[b]} for b in range(nb)]
+
+    def sisso_batch_graph(self, Xs, ys, prm, D, m=1, units=None, use_graph=True):
+        """The batched SISSO loop as one library call (discover_sisso_batch):
+        the first call with given inputs runs eagerly and captures a
+        hipGraph, later calls with the same input tensors replay it.  The
+        output tensors are kept per input set and reused (and overwritten)
+        by later calls.  Returns (ids [nb][D][k], scores [nb][D][k],
+        subsets [nb][D][m][3], rmse [nb][D][m], coef [nb][D][m][4], replayed) with
+        replayed 1 (graph replayed), 0 (eager) or -1 (eager; capture failed)."""
+        torch = self.torch
+        import numpy as np
+        nb = len(Xs)
+        dev = Xs[0].device
+        key = (tuple(x.data_ptr() for x in Xs), tuple(y.data_ptr() for y in ys), D, m, prm.k)
+        cache = self.__dict__.setdefault("_sisso_out", {})
+        if key not in cache:
+            cache[key] = (torch.empty((nb, D, prm.k), dtype=torch.int64, device=dev),
+                          torch.empty((nb, D, prm.k), dtype=torch.float64, device=dev),
+                          torch.empty((nb, D, m, 3), dtype=torch.int32, device=dev),
+                          torch.empty((nb, D, m), dtype=torch.float64, device=dev),
+                          torch.empty((nb, D, m, 4), dtype=torch.float64, device=dev))
+        ids, sc, sub, rmse, coef = cache[key]
+        pbs = (Problem * nb)()
+        keep = []
+        for b in range(nb):
+            x, y = Xs[b], ys[b]
+            assert x.is_contiguous() and y.is_contiguous()
+            p_, n_ = x.shape
+            pbs[b].n, pbs[b].p, pbs[b].T = n_, p_, 1
+            u = units[b] if units is not None else None
+            if u is not None:
+                u = np.ascontiguousarray(u, dtype=np.int32)
+                keep.append(u)
+                pbs[b].B, pbs[b].units = u.shape[1], u.ctypes.data
+            pbs[b].X, pbs[b].ldx = x.data_ptr(), n_
+            pbs[b].Y, pbs[b].ldy = y.data_ptr(), n_
+        rep = C.c_int32(0)
+        _check(lib().discover_sisso_batch(self.h, pbs, nb, C.byref(prm), D, m, 1 if use_graph else 0,
+                                          ids.data_ptr(), sc.data_ptr(), sub.data_ptr(),
+                                          rmse.data_ptr(), coef.data_ptr(), C.byref(rep),
+                                          _stream_handle(torch, dev)))
+        if rep.value < 0:
+            self.capture_error = lib().discover_last_error().decode()
+        return ids, sc, sub, rmse, coef, int(rep.value)
 
     def sisso(self, X, y, prm, D, units=None, n_resid=1, omp_D=0):
         """The SISSO loop: for d = 1..D screen against the residual(s) of the

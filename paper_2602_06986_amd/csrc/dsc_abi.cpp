@@ -20,6 +20,9 @@ extern "C" void discover_destroy(discover_ctx* ctx) {
     if (!ctx) return;
     if (hipSetDevice(ctx->device) == hipSuccess) {
         if (hipDeviceSynchronize() != hipSuccess) { /* keep tearing down */ }
+        ctx->batches.clear();              // captured graphs first, then what they referenced
+        ctx->plans.clear();
+        if (ctx->side && hipStreamDestroy(ctx->side) != hipSuccess) { /* ignore */ }
         for (auto& kv : ctx->bufs)
             if (kv.second.p && hipFree(kv.second.p) != hipSuccess) { /* ignore */ }
         for (auto& p : ctx->pending) {

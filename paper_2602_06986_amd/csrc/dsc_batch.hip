@@ -1,0 +1,250 @@
+// The SISSO dimension loop over a batch of datasets as one launch sequence
+// (the batched form of the screening + sparsifying steps of the cited SISSO
+// method, Summary and Software Description): for d = 1..D every dataset is
+// screened against its residuals, the selected features are appended to its
+// subspace, and exhaustive L0 refits its target.  The first call with a
+// given set of inputs runs eagerly (sizing every buffer and settling every
+// capacity), then captures the same sequence into a hipGraph; later calls
+// with the same inputs replay the graph and check, on the device, that
+// every capacity held and every selection was complete (else they run
+// eagerly again).
+#include "dsc_internal.h"
+
+#include <string>
+
+namespace dsc {
+
+// One thread per check; any failure sets *out.
+__global__ __launch_bounds__(256) void k_verdict(ctab<ListCheck> L, int nl, ctab<BandCheck> B, int nbc,
+                                                 int* __restrict__ out) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    bool bad = false;
+    if (i < nl) {
+        const ListCheck& c = tab(L, i);
+        DSC_GLOBAL(c.res); DSC_GLOBAL(c.ctr);
+        const int64_t* r = c.res;
+        bad = r[4] > c.cap || (c.dedup && r[3] > c.fcap) || !(r[1] || c.K >= c.N) ||
+              (c.ctr[0] & 0xFFFFFFFFull) != 0;
+    } else if (i < nl + nbc) {
+        const BandCheck& c = tab(B, i - nl);
+        DSC_GLOBAL(c.cnt);
+        bad = (int64_t)c.cnt[0] > c.cap || (int64_t)c.cnt[1] > c.cap || c.cnt[0] == 0;
+    }
+    if (bad) atomicOr(out, 1);
+}
+
+struct SissoGraph {
+    int id = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint64_t generation = 0;
+    ~SissoGraph() {
+        if (exec && hipGraphExecDestroy(exec) != hipSuccess) { /* ignore */ }
+        if (graph && hipGraphDestroy(graph) != hipSuccess) { /* ignore */ }
+    }
+};
+
+struct SissoCall {
+    const discover_problem* probs;
+    int nb;
+    discover_screen_params prm;
+    int D, m, k, ldf;
+    int64_t* ids;
+    double* sc;
+    int32_t* sub;
+    double* rmse;
+    double* coef;
+};
+
+// The whole loop on stream st; while capturing, the checks of every
+// selection list and band are collected and judged by k_verdict.
+static void sisso_sequence(discover_ctx* ctx, const SissoCall& c, const std::string& gtag,
+                           hipStream_t st) {
+    const int nb = c.nb, D = c.D, m = c.m, k = c.k;
+    const size_t ldf = (size_t)c.ldf;
+    ctx->tag = gtag;
+    double* F = ctx->buf<double>("sisF" + gtag, (size_t)nb * D * k * ldf);
+    double* R = ctx->buf<double>("sisR" + gtag, (size_t)nb * m * ldf);
+    int* verdict = ctx->buf<int>("sisV" + gtag, 1);
+    std::vector<FillSeg> fills;
+    fills.push_back(fill_seg(verdict, 4, 0u));
+    fills.push_back(fill_seg(c.sub, (size_t)nb * D * m * 3 * 4, 0xFFFFFFFFu));
+    fills.push_back(fill_seg(c.coef, (size_t)nb * D * m * 4 * 8, 0xFFFFFFFFu));   // NaN
+    fill_all(ctx, "sis_fills", fills, st);
+    std::vector<ListCheck> lc;
+    std::vector<BandCheck> bc;
+    std::vector<discover_l0_stats> l0st(nb);
+    for (int d = 1; d <= D; d++) {
+        ctx->tag = gtag + "d" + std::to_string(d);
+        std::vector<discover_problem> sp(c.probs, c.probs + nb);
+        std::vector<ScreenOut> so(nb);
+        for (int b = 0; b < nb; b++) {
+            if (d > 1) {
+                sp[b].Y = R + (size_t)b * m * ldf;
+                sp[b].ldy = (int64_t)ldf;
+                sp[b].T = m;
+            }
+            sp[b].exclude = d > 1 ? c.ids + (int64_t)b * D * k : nullptr;
+            sp[b].n_exclude = (d - 1) * k;
+            const int64_t row = (int64_t)b * D + (d - 1);
+            so[b] = ScreenOut{c.ids + row * k, c.sc + row * k, F + ((size_t)b * D * k + (size_t)(d - 1) * k) * ldf,
+                              (int64_t)ldf};
+        }
+        discover_screen_params q = c.prm;
+        if (d > 1 && m > 1) q.score_mode = DISCOVER_SCORE_MAX;
+        generate_screen(ctx, sp.data(), nb, q, so, nullptr, st, ctx->capturing ? &lc : nullptr);
+        std::vector<discover_l0_problem> lp(nb);
+        std::vector<L0Out> lo(nb);
+        for (int b = 0; b < nb; b++) {
+            lp[b].n = c.probs[b].n;
+            lp[b].S = d * k;
+            lp[b].F = F + (size_t)b * D * k * ldf;
+            lp[b].ldf = (int64_t)ldf;
+            lp[b].ids = c.ids + (int64_t)b * D * k;
+            lp[b].y = c.probs[b].Y;
+            const int64_t row = (int64_t)b * D + (d - 1);
+            lo[b] = L0Out{c.sub + row * m * 3, 3, c.rmse + row * m, c.coef + row * m * 4, 4,
+                          R + (size_t)b * m * ldf, (int64_t)ldf};
+        }
+        l0_batch(ctx, lp.data(), nb, d, m, lo, l0st, st, ctx->capturing ? &bc : nullptr);
+    }
+    ctx->tag = gtag;
+    if (!ctx->capturing) {
+        // one selection list and one band per dataset and dimension: size the
+        // check tables now, a capture may not allocate
+        ctx->raw("sis_lchecks" + gtag, (size_t)D * nb * sizeof(ListCheck));
+        ctx->raw("sis_bchecks" + gtag, (size_t)D * nb * sizeof(BandCheck));
+    } else {
+        const ListCheck* dl = ctx->upload("sis_lchecks", lc, st);
+        const BandCheck* db = ctx->upload("sis_bchecks", bc, st);
+        const int n = (int)(lc.size() + bc.size());
+        k_verdict<<<(unsigned)cdiv(std::max(n, 1), 256), 256, 0, st>>>(ct(dl), (int)lc.size(), ct(db),
+                                                                       (int)bc.size(), verdict);
+        check_launch("k_verdict");
+    }
+    ctx->tag.clear();
+}
+
+static std::string sisso_key(const SissoCall& c) {
+    std::string key((const char*)&c.prm, sizeof c.prm);
+    const int64_t f[9] = {c.nb, c.D, c.m, c.k, (int64_t)(intptr_t)c.ids, (int64_t)(intptr_t)c.sc,
+                          (int64_t)(intptr_t)c.sub, (int64_t)(intptr_t)c.rmse, (int64_t)(intptr_t)c.coef};
+    key.append((const char*)f, sizeof f);
+    for (int b = 0; b < c.nb; b++) {
+        const discover_problem& p = c.probs[b];
+        const int64_t g[7] = {p.n, p.p, p.B, (int64_t)(intptr_t)p.X, p.ldx, (int64_t)(intptr_t)p.Y, p.ldy};
+        key.append((const char*)g, sizeof g);
+        if (p.B && p.units) key.append((const char*)p.units, sizeof(int32_t) * p.p * p.B);
+    }
+    return key;
+}
+
+}  // namespace dsc
+
+extern "C" discover_status discover_sisso_batch(discover_ctx* ctx, const discover_problem* probs,
+                                                int32_t n_problems, const discover_screen_params* prm,
+                                                int32_t D, int32_t m, int32_t use_graph,
+                                                int64_t* out_ids, double* out_scores,
+                                                int32_t* out_subsets, double* out_rmse, double* out_coef,
+                                                int32_t* out_replayed, void* stream) {
+    using namespace dsc;
+    return guarded([&] {
+        DSC_REQUIRE(ctx && probs && prm && n_problems >= 1 && n_problems <= 65535, "ctx/probs/prm");
+        DSC_REQUIRE(D >= 1 && D <= 3, "D = %d outside 1..3", D);
+        DSC_REQUIRE(m >= 1 && m <= DISCOVER_MAX_TARGETS, "m = %d outside 1..%d", m, DISCOVER_MAX_TARGETS);
+        DSC_REQUIRE(out_ids && out_scores && out_subsets && out_rmse && out_coef, "outputs required");
+        DSC_REQUIRE(prm->rung >= 0 && prm->rung <= DISCOVER_MAX_RUNG && prm->k >= 1, "rung/k");
+        DSC_REQUIRE(prm->score_mode == DISCOVER_SCORE_PER_TARGET, "the first dimension screens one target");
+        int nmax = 0;
+        for (int b = 0; b < n_problems; b++) {
+            const discover_problem& p = probs[b];
+            DSC_REQUIRE(p.T == 1, "problem %d: T must be 1 (the target)", b);
+            DSC_REQUIRE(p.n_exclude == 0, "problem %d: exclude lists are built by the loop", b);
+            DSC_REQUIRE(p.n >= D + 2 && p.n >= 3 && p.X && p.Y && p.ldx >= p.n && p.ldy >= p.n,
+                        "problem %d: n/X/Y", b);
+            DSC_REQUIRE(p.p >= 1 && p.p <= 4096 && p.B >= 0 && p.B <= DISCOVER_MAX_UNITS &&
+                        (p.B == 0 || p.units), "problem %d: p/B/units", b);
+            nmax = std::max(nmax, p.n);
+        }
+        DSC_HIP(hipSetDevice(ctx->device));
+        hipStream_t caller = (hipStream_t)stream;
+        if (out_replayed) *out_replayed = 0;
+        SissoCall c{probs, n_problems, *prm, D, m, prm->k, (int)cdiv(nmax, 64) * 64,
+                    out_ids, out_scores, out_subsets, out_rmse, out_coef};
+        // all work runs on the context's own stream (a capture needs a
+        // non-default stream); the call returns with its results ready
+        hipStream_t gs = nullptr;
+        {
+            auto it = ctx->batches.find("sisso_stream");
+            if (it == ctx->batches.end()) {
+                hipStream_t s2;
+                DSC_HIP(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
+                auto holder = std::shared_ptr<void>((void*)s2, [](void* p) {
+                    if (hipStreamDestroy((hipStream_t)p) != hipSuccess) { /* ignore */ }
+                });
+                ctx->batches["sisso_stream"] = holder;
+                gs = s2;
+            } else {
+                gs = (hipStream_t)it->second.get();
+            }
+        }
+        DSC_HIP(hipStreamSynchronize(caller));
+        const std::string key = "sisso" + sisso_key(c);
+        auto git = ctx->batches.find(key);
+        std::shared_ptr<SissoGraph> G;
+        if (git != ctx->batches.end()) G = std::static_pointer_cast<SissoGraph>(git->second);
+        if (use_graph && G && G->exec && G->generation == ctx->generation) {
+            const std::string gtag = "#s" + std::to_string(G->id);
+            int* verdict = ctx->buf<int>("sisV" + gtag, 1);
+            DSC_HIP(hipGraphLaunch(G->exec, gs));
+            int h = 1;
+            DSC_HIP(hipMemcpyAsync(&h, verdict, 4, hipMemcpyDeviceToHost, gs));
+            DSC_HIP(hipStreamSynchronize(gs));
+            if (h == 0) {
+                if (out_replayed) *out_replayed = 1;
+                return;
+            }
+            G->exec = nullptr;                  // fall back to an eager run below
+        }
+        if (!G) {
+            static int next_id = 0;
+            G = std::make_shared<SissoGraph>();
+            G->id = next_id++;
+            if (ctx->batches.size() >= 256) {
+                ctx->batches.clear();
+                ctx->generation++;
+            }
+            ctx->batches[key] = G;
+        }
+        const std::string gtag = "#s" + std::to_string(G->id);
+        sisso_sequence(ctx, c, gtag, gs);
+        DSC_HIP(hipStreamSynchronize(gs));
+        ctx->resolve_timing();
+        if (!use_graph) return;
+        // capture the same sequence for later calls
+        if (G->exec) { if (hipGraphExecDestroy(G->exec) != hipSuccess) { } G->exec = nullptr; }
+        if (G->graph) { if (hipGraphDestroy(G->graph) != hipSuccess) { } G->graph = nullptr; }
+        const uint64_t gen0 = ctx->generation;
+        ctx->capturing = true;
+        DSC_HIP(hipStreamBeginCapture(gs, hipStreamCaptureModeRelaxed));
+        discover_status cap_status = guarded([&] { sisso_sequence(ctx, c, gtag, gs); });
+        hipGraph_t graph = nullptr;
+        const hipError_t ec = hipStreamEndCapture(gs, &graph);
+        ctx->capturing = false;
+        ctx->tag.clear();
+        if (cap_status != DISCOVER_OK || ec != hipSuccess || !graph || ctx->generation != gen0) {
+            if (graph && hipGraphDestroy(graph) != hipSuccess) { }
+            if (cap_status == DISCOVER_OK) {
+                if (ec != hipSuccess) set_error("graph capture failed: %s", hipGetErrorString(ec));
+                else set_error("device memory was reallocated during graph capture");
+            }
+            if (out_replayed) *out_replayed = -1;
+            return;                             // results of the eager run stand; no graph
+        }
+        hipGraphExec_t exec = nullptr;
+        DSC_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+        G->graph = graph;
+        G->exec = exec;
+        G->generation = ctx->generation;
+    });
+}

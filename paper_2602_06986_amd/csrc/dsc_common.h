@@ -92,6 +92,14 @@ struct discover_ctx {
     // allocate, synchronise or copy from the host: buffers must already be
     // large enough and argument tables already uploaded.
     bool capturing = false;
+    // Suffix of argument-table and result-buffer names, so that the calls of
+    // one captured sequence keep tables of their own.
+    std::string tag;
+    // Bumped whenever device memory that a captured graph may reference is
+    // released (a buffer regrown, plans evicted); graphs of an older
+    // generation are discarded instead of replayed.
+    uint64_t generation = 0;
+    hipStream_t side = nullptr;            // private stream for uploads during capture
 
     // Grow-only named device buffer of at least `bytes` bytes.
     void* raw(const std::string& name, size_t bytes) {
@@ -106,6 +114,7 @@ struct discover_ctx {
                 (void)e;
                 b.p = nullptr;
                 b.cap = 0;
+                generation++;
             }
             size_t want = bytes + bytes / 4;
             want = (want + 4095) & ~size_t(4095);
@@ -126,16 +135,25 @@ struct discover_ctx {
     // Device copy of a host argument table.  The copy is skipped when the
     // device buffer already holds exactly these bytes (so a captured
     // sequence reuses the tables of the eager run that preceded it).
-    void* upload(const std::string& name, const void* data, size_t bytes, hipStream_t st) {
+    // While capturing, a table that differs is written at once through a
+    // private stream (not part of the graph): the graph's kernels read it
+    // when they run.
+    void* upload(const std::string& name0, const void* data, size_t bytes, hipStream_t st) {
+        const std::string name = name0 + tag;
         void* d = raw(name, bytes);
         std::vector<char>& sh = shadows[name];
         const bool same = sh.size() == bytes && bytes && std::memcmp(sh.data(), data, bytes) == 0 &&
                           shadow_ptr[name] == d;
         if (!same) {
-            if (capturing)
-                DSC_FAIL(DISCOVER_E_CAPACITY, "argument table %s changed during graph capture",
-                         name.c_str());
-            if (bytes) DSC_HIP(hipMemcpyAsync(d, data, bytes, hipMemcpyHostToDevice, st));
+            if (bytes) {
+                if (capturing) {
+                    if (!side) DSC_HIP(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+                    DSC_HIP(hipMemcpyAsync(d, data, bytes, hipMemcpyHostToDevice, side));
+                    DSC_HIP(hipStreamSynchronize(side));
+                } else {
+                    DSC_HIP(hipMemcpyAsync(d, data, bytes, hipMemcpyHostToDevice, st));
+                }
+            }
             sh.assign((const char*)data, (const char*)data + bytes);
             shadow_ptr[name] = d;
         }

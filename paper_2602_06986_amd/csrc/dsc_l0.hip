@@ -13,6 +13,7 @@
 //      are swept again and every subset with q >= thr is collected.
 //   4. The collected band is refitted by FP64 Householder QR on the raw
 //      data (one workgroup per subset) and ranked by RSS with the tie rule.
+#include "dsc_internal.h"
 #include "dsc_select.h"
 
 #include <algorithm>
@@ -508,7 +509,7 @@ __device__ __forceinline__ void d_rank_models(const int4* __restrict__ band, con
                               const int64_t* __restrict__ ids, const double* __restrict__ yyp,
                               int n, uint8_t* __restrict__ taken, int32_t* __restrict__ out_sub,
                               double* __restrict__ out_rmse, double* __restrict__ out_coef,
-                              int32_t* __restrict__ chosen) {
+                              int32_t* __restrict__ chosen, int sub_ld, int coef_ld) {
     if (threadIdx.x != 0) return;
     const double yy = *yyp;
     const int64_t nb = min((int64_t)*bcnt, bcap);
@@ -542,17 +543,17 @@ __device__ __forceinline__ void d_rank_models(const int4* __restrict__ band, con
         }
         chosen[q] = (int32_t)pick;
         if (pick < 0) {
-            for (int j = 0; j < D; j++) out_sub[q * D + j] = -1;
+            for (int j = 0; j < D; j++) out_sub[q * sub_ld + j] = -1;
             out_rmse[q] = __longlong_as_double(0x7FF8000000000000LL);
-            for (int j = 0; j <= D; j++) out_coef[q * (D + 1) + j] = __longlong_as_double(0x7FF8000000000000LL);
+            for (int j = 0; j <= D; j++) out_coef[q * coef_ld + j] = __longlong_as_double(0x7FF8000000000000LL);
             continue;
         }
         taken[pick] = 1;
         const int4 s = band[pick];
         const int pos[3] = {s.x, s.y, s.z};
-        for (int j = 0; j < D; j++) out_sub[q * D + j] = pos[j];
+        for (int j = 0; j < D; j++) out_sub[q * sub_ld + j] = pos[j];
         out_rmse[q] = sqrt(brss[pick] / n);
-        for (int j = 0; j <= D; j++) out_coef[q * (D + 1) + j] = bcoef[pick * (D + 1) + j];
+        for (int j = 0; j <= D; j++) out_coef[q * coef_ld + j] = bcoef[pick * (D + 1) + j];
     }
 }
 
@@ -561,10 +562,10 @@ __device__ __forceinline__ void d_resid(int n, int D, const double* __restrict__
                                                int64_t ldf, const double* __restrict__ y,
                                                const int32_t* __restrict__ sub,
                                                const double* __restrict__ coef,
-                                               double* __restrict__ out, int64_t ldr) {
+                                               double* __restrict__ out, int64_t ldr, int sub_ld, int coef_ld) {
     const int q = blockIdx.x;
-    const int32_t* s = sub + q * D;
-    const double* c = coef + q * (D + 1);
+    const int32_t* s = sub + q * sub_ld;
+    const double* c = coef + q * coef_ld;
     for (int i = threadIdx.x; i < n; i += 256) {
         if (s[0] < 0) {
             out[q * ldr + i] = __longlong_as_double(0x7FF8000000000000LL);
@@ -636,6 +637,7 @@ struct RefitArgs {
     int32_t* chosen;
     double* out_resid;
     int64_t ldr;
+    int sub_ld, coef_ld;      // row strides of out_sub and out_coef
 };
 
 // grid (persistent blocks, problems)
@@ -650,14 +652,14 @@ __global__ void k_rank_models(ctab<RefitArgs> A) {
     const RefitArgs& a = tab(A, blockIdx.x);
     DSC_GLOBAL(a.F); DSC_GLOBAL(a.y); DSC_GLOBAL(a.band); DSC_GLOBAL(a.bcnt); DSC_GLOBAL(a.scratch); DSC_GLOBAL(a.brss); DSC_GLOBAL(a.bcoef); DSC_GLOBAL(a.ids); DSC_GLOBAL(a.yy); DSC_GLOBAL(a.taken); DSC_GLOBAL(a.out_sub); DSC_GLOBAL(a.out_rmse); DSC_GLOBAL(a.out_coef); DSC_GLOBAL(a.chosen);
     d_rank_models(a.band, a.brss, a.bcoef, a.bcnt, a.bcap, a.D, a.m, a.ids, a.yy, a.n, a.taken,
-                  a.out_sub, a.out_rmse, a.out_coef, a.chosen);
+                  a.out_sub, a.out_rmse, a.out_coef, a.chosen, a.sub_ld, a.coef_ld);
 }
 
 // grid (models, problems)
 __global__ __launch_bounds__(256) void k_resid(ctab<RefitArgs> A) {
     const RefitArgs& a = tab(A, blockIdx.y);
     DSC_GLOBAL(a.F); DSC_GLOBAL(a.y); DSC_GLOBAL(a.out_sub); DSC_GLOBAL(a.out_coef); DSC_GLOBAL(a.out_resid);
-    d_resid(a.n, a.D, a.F, a.ldf, a.y, a.out_sub, a.out_coef, a.out_resid, a.ldr);
+    d_resid(a.n, a.D, a.F, a.ldf, a.y, a.out_sub, a.out_coef, a.out_resid, a.ldr, a.sub_ld, a.coef_ld);
 }
 
 // ------------------------------------------------------------------ OMP
@@ -838,10 +840,31 @@ struct BandMemo {
     std::vector<int64_t> cap;
 };
 
+static size_t band_arena_bytes(const discover_l0_problem* probs, const std::vector<int>& act,
+                               const std::vector<int64_t>& cap, int D, int m, int nblk_refit,
+                               std::vector<std::vector<size_t>>* offs) {
+    Arena br;
+    for (int b : act) {
+        const size_t c = (size_t)cap[b];
+        std::vector<size_t> v;
+        v.push_back(br.add(c * 16));                                   // band
+        v.push_back(br.add(c * 16));                                   // pairs
+        v.push_back(br.add(c * 8));                                    // brss
+        v.push_back(br.add(c * (D + 1) * 8));                          // bcoef
+        v.push_back(br.add(c));                                        // taken
+        v.push_back(br.add((size_t)m * 4));                            // chosen
+        v.push_back(br.add((size_t)nblk_refit * (D + 2) * probs[b].n * 8));  // refit scratch
+        v.push_back(br.add(64));                                       // bcnt, pcnt, st[2], sel[4]
+        v.push_back(br.add(4096 * 4));                                 // hist
+        if (offs) offs->push_back(v);
+    }
+    return br.total;
+}
+
 // Exhaustive L0 of every problem of a call, one launch per phase.
-static void l0_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D, int m,
-                     int32_t* out_sub, double* out_rmse, double* out_coef, double* out_resid,
-                     int64_t ldr, std::vector<discover_l0_stats>& stats, hipStream_t st) {
+void l0_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D, int m,
+              const std::vector<L0Out>& outs, std::vector<discover_l0_stats>& stats,
+              hipStream_t st, std::vector<BandCheck>* checks) {
     // 1. layout
     std::vector<std::shared_ptr<L0Items>> its(nb);
     std::vector<PrepArgs> pa(nb);
@@ -950,23 +973,9 @@ static void l0_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb
     const int nblk_refit = std::max(8, std::min(512, 4096 / nb));
     while (!act.empty()) {
         const int na = (int)act.size();
-        Arena br;
-        std::vector<std::vector<size_t>> bo(na);
-        for (int q = 0; q < na; q++) {
-            const int b = act[q];
-            const size_t c = (size_t)cap[b];
-            auto& v = bo[q];
-            v.push_back(br.add(c * 16));                                   // band
-            v.push_back(br.add(c * 16));                                   // pairs
-            v.push_back(br.add(c * 8));                                    // brss
-            v.push_back(br.add(c * (D + 1) * 8));                          // bcoef
-            v.push_back(br.add(c));                                        // taken
-            v.push_back(br.add((size_t)m * 4));                            // chosen
-            v.push_back(br.add((size_t)nblk_refit * (D + 2) * probs[b].n * 8));  // refit scratch
-            v.push_back(br.add(64));                                       // bcnt, pcnt, st[2], sel[4]
-            v.push_back(br.add(4096 * 4));                                 // hist
-        }
-        char* bb = (char*)ctx->raw("l0_band_arena", br.total);
+        std::vector<std::vector<size_t>> bo;
+        const size_t btot = band_arena_bytes(probs, act, cap, D, m, nblk_refit, &bo);
+        char* bb = (char*)ctx->raw("l0_band_arena" + ctx->tag, btot);
         std::vector<BandArgs> ba(na);
         std::vector<RadixArgs> ra(na);
         std::vector<RefitArgs> fa(na);
@@ -995,10 +1004,10 @@ static void l0_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb
             f.band = g.band; f.bcnt = g.bcnt; f.bcap = cap[b];
             f.scratch = (double*)(bb + v[6]); f.brss = (double*)(bb + v[2]); f.bcoef = (double*)(bb + v[3]);
             f.ids = probs[b].ids; f.yy = pa[b].yy; f.taken = (uint8_t*)(bb + v[4]);
-            f.out_sub = out_sub + (int64_t)b * m * D; f.out_rmse = out_rmse + (int64_t)b * m;
-            f.out_coef = out_coef + (int64_t)b * m * (D + 1); f.chosen = (int32_t*)(bb + v[5]);
-            f.out_resid = out_resid ? out_resid + (int64_t)b * m * ldr : nullptr;
-            f.ldr = ldr;
+            f.out_sub = outs[b].sub; f.sub_ld = outs[b].sub_ld; f.out_rmse = outs[b].rmse;
+            f.out_coef = outs[b].coef; f.coef_ld = outs[b].coef_ld; f.chosen = (int32_t*)(bb + v[5]);
+            f.out_resid = outs[b].resid;
+            f.ldr = outs[b].ldr;
         }
         fill_all(ctx, "l0_fills", fills, st);
         const ctab<BandArgs> dba = ct(ctx->upload("l0_band", ba, st));
@@ -1020,11 +1029,15 @@ static void l0_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb
         }
         k_rank_models<<<na, 64, 0, st>>>(dfa);
         check_launch("k_rank_models");
-        if (out_resid) {
+        if (outs[0].resid) {
             k_resid<<<dim3(m, na), 256, 0, st>>>(dfa);
             check_launch("k_resid");
         }
-        if (ctx->capturing) break;              // capacities are checked after the replay
+        if (ctx->capturing) {                   // capacities are checked after the replay
+            if (checks)
+                for (int q = 0; q < na; q++) checks->push_back(BandCheck{ba[q].bcnt, cap[act[q]]});
+            break;
+        }
         std::vector<unsigned long long> cnt(2 * (size_t)na);
         for (int q = 0; q < na; q++)
             DSC_HIP(hipMemcpyAsync(&cnt[2 * q], ba[q].bcnt, 16, hipMemcpyDeviceToHost, st));
@@ -1043,6 +1056,9 @@ static void l0_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb
         act.swap(next);
     }
     if (!ctx->capturing) {
+        std::vector<int> all(nb);
+        for (int b = 0; b < nb; b++) all[b] = b;
+        ctx->raw("l0_band_arena" + ctx->tag, band_arena_bytes(probs, all, cap, D, m, nblk_refit, nullptr));
         auto bm = std::make_shared<BandMemo>();
         bm->cap = cap;
         if (ctx->batches.size() >= 256) ctx->batches.clear();
@@ -1085,7 +1101,12 @@ extern "C" discover_status discover_l0_fit(discover_ctx* ctx, const discover_l0_
             stats[b] = discover_l0_stats{};
             stats[b].n_subsets = binom(probs[b].S, D);
         }
-        l0_batch(ctx, probs, n_problems, D, m, out_subsets, out_rmse, out_coef, out_resid, ldr, stats, st);
+        std::vector<L0Out> outs(n_problems);
+        for (int b = 0; b < n_problems; b++)
+            outs[b] = L0Out{out_subsets + (int64_t)b * m * D, D, out_rmse + (int64_t)b * m,
+                            out_coef + (int64_t)b * m * (D + 1), D + 1,
+                            out_resid ? out_resid + (int64_t)b * m * ldr : nullptr, ldr};
+        l0_batch(ctx, probs, n_problems, D, m, outs, stats, st);
         if (!ctx->capturing) {
             DSC_HIP(hipStreamSynchronize(st));
             ctx->resolve_timing();

@@ -19,6 +19,7 @@
 //
 // The streamed rung is never materialised: each wave evaluates
 // op(f_i, f_j) for its tile on the fly and keeps only moments in registers.
+#include "dsc_internal.h"
 #include "dsc_select.h"
 #include "dsc_space.h"
 
@@ -1861,7 +1862,10 @@ static std::shared_ptr<Plan> get_plan(discover_ctx* ctx, const discover_problem&
     auto it = ctx->plans.find(key);
     if (it != ctx->plans.end()) return std::static_pointer_cast<Plan>(it->second);
     if (ctx->capturing) DSC_FAIL(DISCOVER_E_CAPACITY, "search-space plan built during graph capture");
-    if (ctx->plans.size() >= 64) ctx->plans.clear();
+    if (ctx->plans.size() >= 64) {
+        ctx->plans.clear();
+        ctx->generation++;
+    }
     auto P = std::make_shared<Plan>();
     P->key = key;
     Space& sp = P->sp;
@@ -2041,7 +2045,6 @@ static void layout_problems(discover_ctx* ctx, const discover_problem* probs, in
         v.push_back(ar.add((size_t)P.TP * ldn * 8));                           // Yn
         v.push_back(ar.add((size_t)P.T * 8));                                  // syy
         v.push_back(ar.add((size_t)P.TP * 8));                                 // ysum
-        v.push_back(ar.add(32));                                               // ctr
         v.push_back(ar.add((size_t)P.Tl * P.N * 8));                           // scores
         v.push_back(ar.add((size_t)P.fix_cap * 8));                            // fix_ids
         v.push_back(ar.add(sp.stream3 ? (size_t)P.fix_cap * 8 : 8));           // fix_ids3
@@ -2054,6 +2057,10 @@ static void layout_problems(discover_ctx* ctx, const discover_problem* probs, in
         v.push_back(ar.add(prm.precision != DISCOVER_FP64 ? (size_t)16 * P.ldl * 2 : 8));  // Ylp
     }
     char* base = (char*)ctx->raw("scr_arena", ar.total);
+    // counters stay apart from the shared arena: a captured run checks the
+    // bad-target flags after later calls have reused the arena
+    unsigned long long* ctr = ctx->buf<unsigned long long>("scr_ctr" + ctx->tag, 4 * (size_t)nb);
+    for (int b = 0; b < nb; b++) PS[b].ctr = ctr + 4 * b;
     for (int b = 0; b < nb; b++) {
         Problem& P = PS[b];
         const auto& v = o[b];
@@ -2063,7 +2070,6 @@ static void layout_problems(discover_ctx* ctx, const discover_problem* probs, in
         P.mu = (double*)at(); P.mur = (double*)at(); P.msq = (double*)at();
         P.valid = (uint8_t*)at();
         P.Yc = (double*)at(); P.Yn = (double*)at(); P.syy = (double*)at(); P.ysum = (double*)at();
-        P.ctr = (unsigned long long*)at();
         P.scores = (double*)at();
         P.fix_ids = (int64_t*)at(); P.fix_ids3 = (int64_t*)at();
         P.Vs = (double*)at(); P.Rs = (double*)at(); P.Cs = (double*)at();
@@ -2383,9 +2389,8 @@ static void screen_all(discover_ctx* ctx, const discover_problem* probs, int nb,
 static void select_round(discover_ctx* ctx, const discover_problem* probs,
                          const discover_screen_params& prm, std::vector<Problem>& PS,
                          const std::vector<ListState>& LS, const std::vector<int>& act,
-                         const std::vector<double>& margin, int64_t* out_ids, double* out_sc,
-                         const std::vector<int64_t>& row, hipStream_t st,
-                         std::vector<SelArgs>& sa) {
+                         const std::vector<double>& margin, const std::vector<ScreenOut>& outs,
+                         hipStream_t st, std::vector<SelArgs>& sa) {
     const int nl = (int)act.size();
     const int k = prm.k;
     Arena ar;
@@ -2411,7 +2416,7 @@ static void select_round(discover_ctx* ctx, const discover_problem* probs,
         v.push_back(ar.add(64));                   // cnt, maxerr, st[2], sel[4]
         v.push_back(ar.add(4096 * 4));             // hist
     }
-    char* base = (char*)ctx->raw("sel_arena", ar.total);
+    char* base = (char*)ctx->raw("sel_arena" + ctx->tag, ar.total);
     sa.assign(nl, SelArgs{});
     std::vector<RadixArgs> ra(nl);
     std::vector<FillSeg> fills;
@@ -2442,8 +2447,8 @@ static void select_round(discover_ctx* ctx, const discover_problem* probs,
         a.k = k; a.dedup = prm.dedup;
         a.Yc = P.Yc; a.syy = P.syy;
         a.excl = pb.exclude; a.n_excl = pb.exclude ? pb.n_exclude : 0;
-        a.out_ids = out_ids + (row[L.b] + L.t) * k;
-        a.out_sc = out_sc + (row[L.b] + L.t) * k;
+        a.out_ids = outs[L.b].ids + (int64_t)L.t * k;
+        a.out_sc = outs[L.b].sc + (int64_t)L.t * k;
         ra[q] = RadixArgs{a.sc, P.N, L.K, hist, sel, stv};
         fills.push_back(fill_seg(misc, 16, 0u));            // pool count, maximum error
         Nmax = std::max(Nmax, P.N);
@@ -2482,6 +2487,20 @@ static void select_round(discover_ctx* ctx, const discover_problem* probs,
         k_groups<<<nl, GRP_THREADS, 0, st>>>(dsa);
         check_launch("k_groups");
     }
+}
+
+// Grow the result arena to what one round over every list needs.
+static void select_reserve(discover_ctx* ctx, const discover_screen_params& prm,
+                           const std::vector<ListState>& LS) {
+    Arena ar;
+    for (const ListState& L : LS) {
+        const size_t cap = (size_t)L.cap, fcap = (size_t)L.fcap;
+        for (size_t b : {cap * 8, cap * 8, cap, cap * 4, cap * 4, cap * 4, (cap + 1) * 8, fcap,
+                         (cap + 1) * 4, (cap + 1) * 4, (cap + 1) * 8, (cap + 1) * 4,
+                         ((size_t)prm.k + 1) * 4, (size_t)64, (size_t)64, (size_t)4096 * 4})
+            ar.add(b);
+    }
+    ctx->raw("sel_arena" + ctx->tag, ar.total);
 }
 
 static void validate(const discover_problem* probs, int32_t nb, const discover_screen_params* prm,
@@ -2534,17 +2553,14 @@ static std::string call_key(const discover_problem* probs, int nb, const discove
     return k;
 }
 
-static void generate_screen(discover_ctx* ctx, const discover_problem* probs, int nb,
-                            const discover_screen_params& prm, int64_t* out_ids, double* out_sc,
-                            double* out_values, int64_t ldv, discover_screen_stats* out_stats,
-                            hipStream_t st) {
+void generate_screen(discover_ctx* ctx, const discover_problem* probs, int nb,
+                     const discover_screen_params& prm, const std::vector<ScreenOut>& outs,
+                     discover_screen_stats* out_stats, hipStream_t st, std::vector<ListCheck>* checks) {
     std::vector<Problem> PS;
     screen_all(ctx, probs, nb, prm, PS, st);
     std::vector<discover_screen_stats> stats(nb);
     std::vector<double> margin(nb);
-    std::vector<int64_t> row(nb);
     std::vector<ListState> LS;
-    int64_t r0 = 0;
     for (int b = 0; b < nb; b++) {
         const Problem& P = PS[b];
         discover_screen_stats& s = stats[b];
@@ -2557,8 +2573,6 @@ static void generate_screen(discover_ctx* ctx, const discover_problem* probs, in
             s.guard_band = lowprec_delta(prm.precision, P.n);
             margin[b] = std::max(margin[b], s.guard_band);
         }
-        row[b] = r0;
-        r0 += P.Tl;
         for (int t = 0; t < P.Tl; t++) {
             ListState L;
             L.b = b; L.t = t;
@@ -2580,8 +2594,16 @@ static void generate_screen(discover_ctx* ctx, const discover_problem* probs, in
     std::vector<SelArgs> sa;
     bool checked_bad = false;
     while (!act.empty()) {
-        select_round(ctx, probs, prm, PS, LS, act, margin, out_ids, out_sc, row, st, sa);
-        if (ctx->capturing) break;              // results are checked after the replay
+        select_round(ctx, probs, prm, PS, LS, act, margin, outs, st, sa);
+        if (ctx->capturing) {                   // results are checked after the replay
+            if (checks)
+                for (size_t q = 0; q < act.size(); q++) {
+                    const ListState& L = LS[act[q]];
+                    checks->push_back(ListCheck{sa[q].res, L.cap, L.fcap, L.K, PS[L.b].N,
+                                                PS[L.b].ctr, prm.dedup});
+                }
+            break;
+        }
         // one synchronisation per round: outcome of every active list
         const int nl = (int)act.size();
         std::vector<int64_t> h_res(8 * (size_t)nl);
@@ -2641,19 +2663,22 @@ static void generate_screen(discover_ctx* ctx, const discover_problem* probs, in
         act.swap(next);
     }
     if (!ctx->capturing) {
+        // size the result arena for a one-round run of every list at the final
+        // capacities, as a captured run does
+        select_reserve(ctx, prm, LS);
         auto m = std::make_shared<SelMemo>();
         for (const ListState& L : LS) { m->K.push_back(L.K); m->cap.push_back(L.cap); m->fcap.push_back(L.fcap); }
         if (ctx->batches.size() >= 256) ctx->batches.clear();
         ctx->batches["sel" + ck] = m;
     }
-    if (out_values) {
+    if (outs[0].vals) {
         std::vector<ValArgs> va;
         int64_t mmax = 0;
         for (int b = 0; b < nb; b++) {
             const Problem& P = PS[b];
             ValArgs a{};
-            a.ids = out_ids + row[b] * prm.k; a.m = (int64_t)P.Tl * prm.k; a.ev = P.ev(); a.o = P.ops();
-            a.n = P.n; a.out = out_values + row[b] * prm.k * ldv; a.ldv = ldv;
+            a.ids = outs[b].ids; a.m = (int64_t)P.Tl * prm.k; a.ev = P.ev(); a.o = P.ops();
+            a.n = P.n; a.out = outs[b].vals; a.ldv = outs[b].ldv;
             va.push_back(a);
             mmax = std::max(mmax, a.m);
         }
@@ -2681,7 +2706,13 @@ extern "C" discover_status discover_generate_screen(discover_ctx* ctx, const dis
         DSC_REQUIRE(ctx, "ctx is NULL");
         validate(probs, n_problems, prm, out_ids, out_scores, out_values, ldv);
         DSC_HIP(hipSetDevice(ctx->device));
-        generate_screen(ctx, probs, n_problems, *prm, out_ids, out_scores, out_values, ldv, out_stats,
-                        (hipStream_t)stream);
+        std::vector<ScreenOut> outs(n_problems);
+        int64_t row = 0;
+        for (int b = 0; b < n_problems; b++) {
+            outs[b] = ScreenOut{out_ids + row * prm->k, out_scores + row * prm->k,
+                                out_values ? out_values + row * prm->k * ldv : nullptr, ldv};
+            row += prm->score_mode == DISCOVER_SCORE_MAX ? 1 : probs[b].T;
+        }
+        generate_screen(ctx, probs, n_problems, *prm, outs, out_stats, (hipStream_t)stream);
     });
 }

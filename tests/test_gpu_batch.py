@@ -137,3 +137,42 @@ def test_batch128_sisso_vs_oracle(torch, ctx, D, oracle_mod):
             assert win == sorted(rd["models"][0]["ids"]), w["name"]
             r_ref = rd["models"][0]["rmse"]
             assert abs(float(gd["rmse"][0]) - r_ref) <= 1e-10 * r_ref + 1e-13 * np.std(w["Y"][0])
+
+
+def test_sisso_batch_graph_replays_match_eager(torch, ctx, D):
+    """discover_sisso_batch: the eager first call, then several replays of
+    its captured graph (with other GPU work and synchronisations between
+    them) all give exactly the batched Python loop's selections and models."""
+    rng = np.random.default_rng(77)
+    Xs, ys = [], []
+    for b in range(6):
+        p, n = int(rng.integers(4, 8)), int(rng.integers(40, 400))
+        X = rng.uniform(0.5, 2.0, size=(p, n))
+        y = 1.0 + 2.0 * X[0] * X[1] - 0.5 * X[2] / X[-1] + 0.01 * rng.normal(size=n)
+        Xs.append(dev(torch, X))
+        ys.append(dev(torch, y))
+    prm = D.params(rung=2, k=15)
+    Dd = 3
+    ref = ctx.sisso_batch(Xs, ys, prm, Dd)
+    results = []
+    for call in range(4):
+        ids, sc, sub, rmse, coef, replayed = ctx.sisso_batch_graph(Xs, ys, prm, Dd)
+        assert replayed == (1 if call > 0 else 0), (call, replayed, getattr(ctx, "capture_error", ""))
+        results.append([t.clone() for t in (ids, sc, sub, rmse, coef)])
+        # other work and synchronisations between replays
+        junk = torch.ones(1 << 20, device="cuda").cumsum(0)
+        torch.cuda.synchronize()
+        del junk
+    for b in range(6):
+        for d in range(Dd):
+            rd = ref[b]["dims"][d]
+            exp_ids = rd["sel_ids"].cpu().numpy()
+            exp_sub = rd["subsets"][0].cpu().numpy()
+            for res in results:
+                ids, sc, sub, rmse, coef = res
+                assert np.array_equal(ids[b, d].cpu().numpy(), exp_ids), (b, d)
+                assert np.array_equal(_bits(sc[b, d]), _bits(rd["sel_scores"])), (b, d)
+                assert np.array_equal(sub[b, d, 0, :d + 1].cpu().numpy(), exp_sub), (b, d)
+                assert bool((sub[b, d, 0, d + 1:] == -1).all())
+                assert np.array_equal(_bits(rmse[b, d, :1]), _bits(rd["rmse"][:1])), (b, d)
+                assert np.array_equal(_bits(coef[b, d, 0, :d + 2]), _bits(rd["coef"][0])), (b, d)
