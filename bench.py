@@ -55,6 +55,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="units16", choices=("units16", "batch128"),
+                    help="units16 (default): one 16-feature unit dataset; batch128: 128 datasets "
+                         "of uneven size, plain per-dataset loop vs batched vs graph-replayed")
     ap.add_argument("--no-oracle", action="store_true", help="skip the parity gate and CPU baseline")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device-to-device copy of MIB MiB (the reference "
@@ -79,12 +82,123 @@ def oracle_step(w, omp_D):
     return ref, dt, screened + subsets, int(O.lib().or_max_threads())
 
 
+def batch_main(args):
+    """128 datasets (n ~ U{50..2000}, p ~ U{6..20}, rung 2, top-200, L0 D<=3):
+    the same work three ways -- one sisso() call per dataset, the batched
+    loop (one screening and one L0 call per dimension for all datasets) and
+    discover_sisso_batch replaying its captured graph.  value = items of the
+    whole batch per second of the graph-replayed run."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_2602_06986_amd as Dm
+
+    ws = synth.batch128()
+    dev = torch.device("cuda:0")
+    Xs = [torch.as_tensor(w["X"], device=dev) for w in ws]
+    ys = [torch.as_tensor(w["Y"][0], device=dev).contiguous() for w in ws]
+    prm = Dm.params(ops=ws[0]["ops"], rung=2, k=ws[0]["k"])
+    D = ws[0]["D"]
+    ctx = Dm.Context(0)
+
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            out = fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            out = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps, out
+
+    plain_steps = max(1, min(args.steps, 3))
+    t_plain, plain = timed(lambda: [ctx.sisso(Xs[b], ys[b], prm, D) for b in range(len(ws))],
+                           plain_steps, 1)
+    t_batch, batched = timed(lambda: ctx.sisso_batch(Xs, ys, prm, D), args.steps, args.warmup)
+    replays = []
+
+    def graph_step():
+        r = ctx.sisso_batch_graph(Xs, ys, prm, D)
+        replays.append(r[5])
+        return r
+
+    ctx.set_timing(True)
+    ctx.reset_timing()
+    t_graph, g = timed(graph_step, args.steps, max(args.warmup, 2))
+    ctx.set_timing(False)
+    ids, sc, sub, rmse, coef, rep = g
+    # identical selections and winners in all three forms
+    same = True
+    for b in range(len(ws)):
+        S_plain = plain[b]["S_ids"].cpu().numpy()
+        S_batch = batched[b]["S_ids"].cpu().numpy()
+        same &= np.array_equal(S_plain, S_batch)
+        same &= np.array_equal(ids[b].reshape(-1).cpu().numpy(), S_plain)
+        for d in range(D):
+            pd, bd = plain[b]["dims"][d], batched[b]["dims"][d]
+            same &= np.array_equal(pd["subsets"].cpu().numpy(), bd["subsets"].cpu().numpy())
+            same &= np.array_equal(pd["subsets"][0].cpu().numpy(), sub[b, d, 0, :d + 1].cpu().numpy())
+            same &= bool((pd["rmse"] == bd["rmse"]).all()) and float(pd["rmse"][0]) == float(rmse[b, d, 0])
+    screened = sum(d["screen_stats"]["n_unit_valid"] for r in batched for d in r["dims"])
+    subsets = sum(d["l0_stats"]["n_subsets"] for r in batched for d in r["dims"])
+    items = screened + subsets
+    kern = {}
+    for name in ("materialise", "screen_list", "screen_pairs", "select", "rescore", "sort_dedup",
+                 "dedup_pairs", "values", "l0_gram", "l0_table", "l0_sweep", "l0_sweep3", "l0_band",
+                 "l0_refit"):
+        n, t = ctx.timing(name)
+        if n:
+            kern[name] = {"launches": n, "ms_total": t}
+    line = {
+        "metric": "candidates screened/s + L0 subsets fitted/s, exact top-k vs FP64 oracle",
+        "value": items / t_graph, "unit": "items/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": t_graph * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "batch128: 128 datasets, n ~ U{50..2000}, p ~ U{6..20} uniform(0.5,2) "
+                               "dimensionless, rung 2, SIS top-200, L0 D<=3, planted 3-term targets",
+                   "candidates_screened": screened, "subsets_fitted": subsets},
+        "plain_loop_ms": t_plain * 1e3, "batched_eager_ms": t_batch * 1e3, "graph_ms": t_graph * 1e3,
+        "speedup_batched_vs_plain": t_plain / t_batch, "speedup_graph_vs_plain": t_plain / t_graph,
+        "graph_replayed": all(r == 1 for r in replays[1:]),
+        "identical_selections": bool(same),
+        "kernels_eager_first_call": kern,
+    }
+    if not args.no_oracle:
+        from oracle import oracle as O
+        pick = list(range(0, len(ws), 16))
+        ok = True
+        t0 = time.perf_counter()
+        for b in pick:
+            ref = O.sisso(ws[b])
+            S_g = batched[b]["S_ids"].cpu().numpy()
+            for rd, gd in zip(ref["dims"], batched[b]["dims"]):
+                ok &= set(gd["sel_ids"].cpu().numpy().tolist()) == set(rd["sel_ids"].tolist())
+                win = sorted(int(S_g[i]) for i in gd["subsets"][0].cpu().numpy())
+                ok &= win == sorted(rd["models"][0]["ids"])
+        t_cpu = time.perf_counter() - t0
+        line["parity"] = "pass" if ok and same else "FAIL"
+        samp_items = 0
+        for b in pick:
+            r = batched[b]
+            samp_items += sum(d["screen_stats"]["n_unit_valid"] + d["l0_stats"]["n_subsets"]
+                              for d in r["dims"])
+        line["cpu_baseline"] = {"value": samp_items / t_cpu, "unit": "items/s",
+                                "cores": int(O.lib().or_max_threads()), "kind": "oracle",
+                                "sample": "the oracle's whole loop on datasets %s (%d items) in %.2f s"
+                                          % (pick, samp_items, t_cpu)}
+        if not (ok and same):
+            line["value"] = None
+    print(json.dumps(line))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build measures the single-GPU path "
               "(--gpus %d requested); multi-GPU sharding is described in DESIGN.md" % args.gpus)
         sys.exit(2)
+    if args.workload == "batch128":
+        return batch_main(args)
     import numpy as np
     import torch
     import synth

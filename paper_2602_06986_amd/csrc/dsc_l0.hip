@@ -476,31 +476,6 @@ __device__ void block_lsq(int n, int d, const int* idx, const double* __restrict
     }
 }
 
-// One workgroup per band entry (persistent over the band).
-__device__ __forceinline__ void d_refit(int n, int D, const double* __restrict__ F,
-                                               int64_t ldf, const double* __restrict__ y,
-                                               const int4* __restrict__ band,
-                                               const unsigned long long* __restrict__ bcnt,
-                                               int64_t bcap,
-                                               double* __restrict__ scratch,
-                                               double* __restrict__ brss,
-                                               double* __restrict__ bcoef) {
-    __shared__ double coef[DISCOVER_MAX_D + 1];
-    __shared__ double rss;
-    double* A = scratch + (int64_t)blockIdx.x * (D + 2) * n;
-    const int64_t nb = min((int64_t)*bcnt, bcap);
-    for (int64_t e = blockIdx.x; e < nb; e += gridDim.x) {
-        const int4 s = band[e];
-        const int idx[3] = {s.x, s.y, s.z};
-        block_lsq(n, D, idx, F, ldf, y, A, coef, &rss, nullptr);
-        if (threadIdx.x == 0) {
-            brss[e] = rss;
-            for (int j = 0; j <= D; j++) bcoef[e * (D + 1) + j] = coef[j];
-        }
-        __syncthreads();
-    }
-}
-
 // Rank the band (one thread): repeatedly take the minimum RSS; entries
 // within TAU_TIE * yy of it are tied and the smallest sorted-ID tuple wins.
 __device__ __forceinline__ void d_rank_models(const int4* __restrict__ band, const double* __restrict__ brss,
@@ -640,11 +615,65 @@ struct RefitArgs {
     int sub_ld, coef_ld;      // row strides of out_sub and out_coef
 };
 
-// grid (persistent blocks, problems)
-__global__ __launch_bounds__(256) void k_refit(ctab<RefitArgs> A) {
-    const RefitArgs& a = tab(A, blockIdx.y);
-    DSC_GLOBAL(a.F); DSC_GLOBAL(a.y); DSC_GLOBAL(a.band); DSC_GLOBAL(a.bcnt); DSC_GLOBAL(a.scratch); DSC_GLOBAL(a.brss); DSC_GLOBAL(a.bcoef); DSC_GLOBAL(a.ids); DSC_GLOBAL(a.yy); DSC_GLOBAL(a.taken); DSC_GLOBAL(a.out_sub); DSC_GLOBAL(a.out_rmse); DSC_GLOBAL(a.out_coef); DSC_GLOBAL(a.chosen);
-    d_refit(a.n, a.D, a.F, a.ldf, a.y, a.band, a.bcnt, a.bcap, a.scratch, a.brss, a.bcoef);
+// Offsets of every problem's band in one merged work list: boff[p] =
+// sum of min(count, capacity) over problems before p (one block).
+__global__ __launch_bounds__(256) void k_band_offsets(ctab<RefitArgs> A, int na, int64_t* __restrict__ boff) {
+    __shared__ int64_t part[256];
+    const int per = (na + 255) / 256;
+    const int b0 = threadIdx.x * per, b1 = min(na, b0 + per);
+    int64_t s = 0;
+    for (int b = b0; b < b1; b++) {
+        const RefitArgs& a = tab(A, b);
+        s += min((int64_t)*a.bcnt, a.bcap);
+    }
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t acc = 0;
+        for (int t = 0; t < 256; t++) {
+            const int64_t v = part[t];
+            part[t] = acc;
+            acc += v;
+        }
+        boff[na] = acc;
+    }
+    __syncthreads();
+    int64_t acc = part[threadIdx.x];
+    for (int b = b0; b < b1; b++) {
+        boff[b] = acc;
+        const RefitArgs& a = tab(A, b);
+        acc += min((int64_t)*a.bcnt, a.bcap);
+    }
+}
+
+// QR refit of every band entry of every problem: persistent workgroups
+// take entries from the merged list, so one problem with a large band is
+// spread over the whole GPU.
+__global__ __launch_bounds__(256) void k_refit_all(ctab<RefitArgs> A, int na,
+                                                   const int64_t* __restrict__ boff,
+                                                   double* __restrict__ scratch, int64_t sld) {
+    __shared__ double coef[DISCOVER_MAX_D + 1];
+    __shared__ double rss;
+    double* S = scratch + (int64_t)blockIdx.x * sld;
+    const int64_t total = boff[na];
+    for (int64_t e = blockIdx.x; e < total; e += gridDim.x) {
+        int lo = 0, hi = na;                     // boff[lo] <= e < boff[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) / 2;
+            if (boff[mid] <= e) lo = mid; else hi = mid;
+        }
+        const RefitArgs& a = tab(A, lo);
+        DSC_GLOBAL(a.F); DSC_GLOBAL(a.y); DSC_GLOBAL(a.band); DSC_GLOBAL(a.brss); DSC_GLOBAL(a.bcoef);
+        const int64_t le = e - boff[lo];
+        const int4 s = a.band[le];
+        const int idx[3] = {s.x, s.y, s.z};
+        block_lsq(a.n, a.D, idx, a.F, a.ldf, a.y, S, coef, &rss, nullptr);
+        if (threadIdx.x == 0) {
+            a.brss[le] = rss;
+            for (int j = 0; j <= a.D; j++) a.bcoef[le * (a.D + 1) + j] = coef[j];
+        }
+        __syncthreads();
+    }
 }
 
 // grid (problems), 64 threads
@@ -840,9 +869,8 @@ struct BandMemo {
     std::vector<int64_t> cap;
 };
 
-static size_t band_arena_bytes(const discover_l0_problem* probs, const std::vector<int>& act,
-                               const std::vector<int64_t>& cap, int D, int m, int nblk_refit,
-                               std::vector<std::vector<size_t>>* offs) {
+static size_t band_arena_bytes(const std::vector<int>& act, const std::vector<int64_t>& cap, int D,
+                               int m, std::vector<std::vector<size_t>>* offs) {
     Arena br;
     for (int b : act) {
         const size_t c = (size_t)cap[b];
@@ -853,7 +881,6 @@ static size_t band_arena_bytes(const discover_l0_problem* probs, const std::vect
         v.push_back(br.add(c * (D + 1) * 8));                          // bcoef
         v.push_back(br.add(c));                                        // taken
         v.push_back(br.add((size_t)m * 4));                            // chosen
-        v.push_back(br.add((size_t)nblk_refit * (D + 2) * probs[b].n * 8));  // refit scratch
         v.push_back(br.add(64));                                       // bcnt, pcnt, st[2], sel[4]
         v.push_back(br.add(4096 * 4));                                 // hist
         if (offs) offs->push_back(v);
@@ -970,11 +997,16 @@ void l0_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D
     }
     std::vector<int> act(nb);
     for (int b = 0; b < nb; b++) act[b] = b;
-    const int nblk_refit = std::max(8, std::min(512, 4096 / nb));
+    constexpr int NREFIT = 2048;                // persistent refit workgroups (all problems)
+    int nmax = 0;
+    for (int b = 0; b < nb; b++) nmax = std::max(nmax, probs[b].n);
+    const int64_t sld = (int64_t)(D + 2) * nmax;
+    double* rscratch = ctx->buf<double>("l0_refit_scratch", (size_t)NREFIT * sld);
+    int64_t* boff = ctx->buf<int64_t>("l0_boff" + ctx->tag, (size_t)nb + 1);
     while (!act.empty()) {
         const int na = (int)act.size();
         std::vector<std::vector<size_t>> bo;
-        const size_t btot = band_arena_bytes(probs, act, cap, D, m, nblk_refit, &bo);
+        const size_t btot = band_arena_bytes(act, cap, D, m, &bo);
         char* bb = (char*)ctx->raw("l0_band_arena" + ctx->tag, btot);
         std::vector<BandArgs> ba(na);
         std::vector<RadixArgs> ra(na);
@@ -984,7 +1016,7 @@ void l0_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D
         for (int q = 0; q < na; q++) {
             const int b = act[q];
             const auto& v = bo[q];
-            char* misc = bb + v[7];
+            char* misc = bb + v[6];
             BandArgs& g = ba[q];
             g = BandArgs{};
             g.G = pa[b].G; g.ldg = pa[b].ldg; g.S = probs[b].S; g.D = D; g.E = pa[b].E; g.lde = pa[b].lde;
@@ -994,7 +1026,7 @@ void l0_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D
             g.sel = (uint32_t*)(misc + 32); g.st = (int64_t*)(misc + 16);
             g.band = (int4*)(bb + v[0]); g.bcnt = (unsigned long long*)misc; g.bcap = cap[b];
             g.pairs = (int4*)(bb + v[1]); g.pcnt = (unsigned long long*)misc + 1; g.pcap = cap[b];
-            ra[q] = RadixArgs{g.lane_q, g.n_lanes, m, (uint32_t*)(bb + v[8]), (uint32_t*)(misc + 32),
+            ra[q] = RadixArgs{g.lane_q, g.n_lanes, m, (uint32_t*)(bb + v[7]), (uint32_t*)(misc + 32),
                               (int64_t*)(misc + 16)};
             fills.push_back(fill_seg(misc, 16, 0u));
             lanes_max = std::max(lanes_max, g.n_lanes);
@@ -1002,7 +1034,7 @@ void l0_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D
             f = RefitArgs{};
             f.n = probs[b].n; f.D = D; f.m = m; f.F = probs[b].F; f.ldf = probs[b].ldf; f.y = probs[b].y;
             f.band = g.band; f.bcnt = g.bcnt; f.bcap = cap[b];
-            f.scratch = (double*)(bb + v[6]); f.brss = (double*)(bb + v[2]); f.bcoef = (double*)(bb + v[3]);
+            f.scratch = nullptr; f.brss = (double*)(bb + v[2]); f.bcoef = (double*)(bb + v[3]);
             f.ids = probs[b].ids; f.yy = pa[b].yy; f.taken = (uint8_t*)(bb + v[4]);
             f.out_sub = outs[b].sub; f.sub_ld = outs[b].sub_ld; f.out_rmse = outs[b].rmse;
             f.out_coef = outs[b].coef; f.coef_ld = outs[b].coef_ld; f.chosen = (int32_t*)(bb + v[5]);
@@ -1024,7 +1056,8 @@ void l0_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D
         }
         {
             KTimer kt(ctx, st, "l0_refit");
-            k_refit<<<dim3(nblk_refit, na), 256, 0, st>>>(dfa);
+            k_band_offsets<<<1, 256, 0, st>>>(dfa, na, boff);
+            k_refit_all<<<NREFIT, 256, 0, st>>>(dfa, na, boff, rscratch, sld);
             check_launch("k_refit");
         }
         k_rank_models<<<na, 64, 0, st>>>(dfa);
@@ -1058,7 +1091,7 @@ void l0_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D
     if (!ctx->capturing) {
         std::vector<int> all(nb);
         for (int b = 0; b < nb; b++) all[b] = b;
-        ctx->raw("l0_band_arena" + ctx->tag, band_arena_bytes(probs, all, cap, D, m, nblk_refit, nullptr));
+        ctx->raw("l0_band_arena" + ctx->tag, band_arena_bytes(all, cap, D, m, nullptr));
         auto bm = std::make_shared<BandMemo>();
         bm->cap = cap;
         if (ctx->batches.size() >= 256) ctx->batches.clear();

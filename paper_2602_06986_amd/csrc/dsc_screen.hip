@@ -500,7 +500,7 @@ __global__ __launch_bounds__(256) void k_screen_pairs(ctab<PairArgs> A,
     const PairArgs& g = tab(A, tile.x);
     DSC_GLOBAL(g.ilist); DSC_GLOBAL(g.Vs); DSC_GLOBAL(g.Rs); DSC_GLOBAL(g.Cs); DSC_GLOBAL(g.Vf); DSC_GLOBAL(g.Rf); DSC_GLOBAL(g.Cf); DSC_GLOBAL(g.mu); DSC_GLOBAL(g.mur); DSC_GLOBAL(g.valid);
     DSC_GLOBAL(g.mat_raw); DSC_GLOBAL(g.Yn); DSC_GLOBAL(g.ysum); DSC_GLOBAL(g.scores); DSC_GLOBAL(g.nscored); DSC_GLOBAL(g.fix_ids); DSC_GLOBAL(g.fix_cnt); DSC_GLOBAL(g.msq);
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: scalar loop
     const int lane = threadIdx.x & 63;
     const int jc0 = tile.y;
     int i;
@@ -544,6 +544,7 @@ __global__ __launch_bounds__(256) void k_screen_pairs(ctab<PairArgs> A,
     const double* __restrict__ Cs = g.Cs;
     const int chunk = (g.n + PAIR_SPLIT - 1) / PAIR_SPLIT;
     const int s_lo = min(g.n, wave * chunk), s_hi = min(g.n, s_lo + chunk);
+#pragma unroll 2
     for (int s = s_lo; s < s_hi; s++) {
         const int64_t so = (int64_t)s * g.ldm + ic;
         const double a = (OPS & 28) ? Vs[so] : 0.0;
