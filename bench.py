@@ -55,9 +55,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="units16", choices=("units16", "batch128"),
+    ap.add_argument("--workload", default="units16", choices=("units16", "batch128", "large24"),
                     help="units16 (default): one 16-feature unit dataset; batch128: 128 datasets "
-                         "of uneven size, plain per-dataset loop vs batched vs graph-replayed")
+                         "of uneven size, plain per-dataset loop vs batched vs graph-replayed; "
+                         "large24: 24 features with units, rung 2 + operator-limited rung 3, "
+                         "8 residuals, top-1000, L0 D<=3, OMP to 6, FP64 vs BF16/FP16 screening")
     ap.add_argument("--no-oracle", action="store_true", help="skip the parity gate and CPU baseline")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device-to-device copy of MIB MiB (the reference "
@@ -191,6 +193,101 @@ def batch_main(args):
     print(json.dumps(line))
 
 
+def large_main(args):
+    """One step of the large configuration (n = 2000, p = 24 with units,
+    rung 2 plus an operator-limited rung 3: 702,860,274 raw candidates per
+    dimension, 8 residual targets with the max score from d = 2, SIS
+    top-1000, exhaustive L0 over the 3000-feature union, OMP to 6) with
+    plain FP64 screening and with the BF16 and FP16 precision forms; the
+    three must select identically.  value = items per second of the BF16
+    step."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_2602_06986_amd as Dm
+
+    w = synth.large24()
+    dev = torch.device("cuda:0")
+    X = torch.as_tensor(w["X"], device=dev)
+    y = torch.as_tensor(w["Y"][0], device=dev)
+    ctx = Dm.Context(0)
+    res = {}
+    for name, prec in (("fp64", Dm.FP64), ("bf16", Dm.BF16_GUARD), ("fp16", Dm.FP16_GUARD)):
+        prm = Dm.params(ops=w["ops"], rung=w["rung"], k=w["k"], rung_ops=w["rung_ops"],
+                        rung_pool=w["rung_pool"], precision=prec)
+
+        def step():
+            return ctx.sisso(X, y, prm, w["D"], units=w["units"], n_resid=w["n_resid"],
+                             omp_D=w["omp_D"])
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        ctx.set_timing(True)
+        ctx.reset_timing()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            out = step()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        ctx.set_timing(False)
+        kern = {}
+        for kn in ("materialise", "screen_list", "screen_pairs", "screen_pairs_list", "screen_lp",
+                   "screen_r3", "screen_fixup", "select", "rescore", "sort_dedup", "dedup_pairs",
+                   "values", "l0_gram", "l0_table", "l0_sweep", "l0_sweep3", "l0_band", "l0_refit",
+                   "omp"):
+            n, t = ctx.timing(kn)
+            if n:
+                kern[kn] = {"launches_per_step": n / args.steps, "ms_per_step": t / args.steps}
+        res[name] = (dt, out, kern)
+        print("large24 %s: %.1f ms per step" % (name, dt * 1e3), file=sys.stderr, flush=True)
+    dt, out, kern = res["bf16"]
+    screened = sum(d["screen_stats"]["n_unit_valid"] for d in out["dims"])
+    subsets = sum(d["l0_stats"]["n_subsets"] for d in out["dims"])
+    same = True
+    ref = res["fp64"][1]
+    for name in ("bf16", "fp16"):
+        o = res[name][1]
+        same &= np.array_equal(o["S_ids"].cpu().numpy(), ref["S_ids"].cpu().numpy())
+        for a, b in zip(o["dims"], ref["dims"]):
+            same &= np.array_equal(a["subsets"].cpu().numpy(), b["subsets"].cpu().numpy())
+        same &= np.array_equal(o["omp"]["active"].cpu().numpy(), ref["omp"]["active"].cpu().numpy())
+    err = {name: max(d["screen_stats"]["max_lowprec_err"] for d in res[name][1]["dims"])
+           for name in ("bf16", "fp16")}
+    band = {name: max(d["screen_stats"]["guard_band"] for d in res[name][1]["dims"])
+            for name in ("bf16", "fp16")}
+    # dominant kernel: the rung-3 FP64 screen (8 residuals at d = 2, 3)
+    r3 = kern.get("screen_r3")
+    roof = None
+    if r3:
+        # algorithmic FP64 work: per unit-valid rung-3 candidate and sample,
+        # the operator, sum, sum of squares and T dot products: 4 + 2T flop
+        st = [d["screen_stats"] for d in out["dims"]]
+        valid3 = 116840512
+        flops = sum(valid3 * w["n"] * (4 + 2 * (1 if i == 0 else w["n_resid"])) for i in range(len(st)))
+        ach = flops / (r3["ms_per_step"] * 1e-3)
+        roof = {"kernel": "k_screen_r3 (FP64 rung-3 screen)", "bound": "alu", "achieved": ach / 1e12,
+                "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": ach / PEAK_FP64, "traffic": None}
+    line = {
+        "metric": "candidates screened/s + L0 subsets fitted/s, exact top-k vs FP64 oracle",
+        "value": (screened + subsets) / dt, "unit": "items/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16+f64", "data": "synthetic",
+        "config": {"workload": "large24: n=2000, p=24 lognormal(0,0.5) over 3 base units, rung 2 + "
+                               "operator-limited rung 3 (702,860,274 raw / 118,424,801 unit-valid), "
+                               "8 residuals (max score), SIS top-1000, L0 D<=3 over 3000, OMP to 6",
+                   "candidates_screened_per_step": screened, "subsets_fitted_per_step": subsets},
+        "ms_per_step_fp64": res["fp64"][0] * 1e3, "ms_per_step_bf16": res["bf16"][0] * 1e3,
+        "ms_per_step_fp16": res["fp16"][0] * 1e3,
+        "speedup_bf16_vs_fp64": res["fp64"][0] / res["bf16"][0],
+        "speedup_fp16_vs_fp64": res["fp64"][0] / res["fp16"][0],
+        "identical_selections": bool(same), "max_lowprec_err": err, "guard_band": band,
+        "kernels_bf16": kern, "kernels_fp64": res["fp64"][2], "roofline": roof,
+    }
+    if not same:
+        line["value"] = None
+    print(json.dumps(line))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -199,6 +296,8 @@ def main():
         sys.exit(2)
     if args.workload == "batch128":
         return batch_main(args)
+    if args.workload == "large24":
+        return large_main(args)
     import numpy as np
     import torch
     import synth

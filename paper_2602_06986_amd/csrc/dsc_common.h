@@ -236,6 +236,11 @@ __device__ __forceinline__ double wave_max(double v) {
 
 __host__ __device__ __forceinline__ int64_t choose2(int64_t m) { return m * (m - 1) / 2; }
 
+// Index of the calling wave in its 256-thread block, as a wave-uniform
+// value (the compiler then keeps per-wave work indices, their loads and
+// their branches on the scalar unit).
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
 // ------------------------------------------------------ argument tables
 // Per-problem argument tables live in device memory and are read through
 // the constant address space, as kernel arguments are: uniform fields become

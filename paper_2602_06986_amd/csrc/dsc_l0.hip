@@ -31,7 +31,7 @@ __device__ __forceinline__ void d_l0_prep(int n, int S, const double* __restrict
                                                  int64_t ldf, const double* __restrict__ y,
                                                  int ldz, double* __restrict__ Z,
                                                  double* __restrict__ yy) {
-    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int row = blockIdx.x * 4 + wave_id();
     const int lane = threadIdx.x & 63;
     if (row > S) return;
     const double* f = row < S ? F + (int64_t)row * ldf : y;
@@ -126,7 +126,7 @@ __device__ __forceinline__ double fast_rcp(double x) {
 __global__ __launch_bounds__(256) void k_sweep1(ctab<SweepArgs> A, const int* __restrict__ bprob) {
     const SweepArgs& g = tab(A, bprob[blockIdx.x]);
     DSC_GLOBAL(g.G); DSC_GLOBAL(g.items); DSC_GLOBAL(g.lane_q);
-    const int64_t it = ((int64_t)blockIdx.x - g.item0) * 4 + (threadIdx.x >> 6);
+    const int64_t it = ((int64_t)blockIdx.x - g.item0) * 4 + wave_id();
     if (it >= g.n_items) return;
     const int lane = threadIdx.x & 63;
     const int a = g.items[it].y + lane;
@@ -153,7 +153,7 @@ __device__ __forceinline__ double q2(const double* G, int ldg, int S, int a, int
 __global__ __launch_bounds__(256) void k_sweep2(ctab<SweepArgs> A, const int* __restrict__ bprob) {
     const SweepArgs& g = tab(A, bprob[blockIdx.x]);
     DSC_GLOBAL(g.G); DSC_GLOBAL(g.items); DSC_GLOBAL(g.lane_q);
-    const int64_t it = ((int64_t)blockIdx.x - g.item0) * 4 + (threadIdx.x >> 6);
+    const int64_t it = ((int64_t)blockIdx.x - g.item0) * 4 + wave_id();
     if (it >= g.n_items) return;
     const int lane = threadIdx.x & 63;
     const int a = g.items[it].x, b = g.items[it].y + lane;
@@ -384,7 +384,7 @@ __global__ __launch_bounds__(256) void k_band_expand3(ctab<BandArgs> A) {
     const double thr = band_thr(g);
     const int64_t np = min((int64_t)*g.pcnt, g.pcap);
     const int lane = threadIdx.x & 63;
-    for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < np; i += (int64_t)gridDim.x * 4) {
+    for (int64_t i = (int64_t)blockIdx.x * 4 + wave_id(); i < np; i += (int64_t)gridDim.x * 4) {
         const int a = g.pairs[i].x, c = g.pairs[i].y;
         const int blo = max(a + 1, g.pairs[i].z), bhi = min(c, g.pairs[i].w);
         const double* Ga = g.G + (int64_t)a * g.ldg;
@@ -698,7 +698,7 @@ __global__ __launch_bounds__(256) void k_omp_corr(int n, int S, const double* __
                                                   const int32_t* __restrict__ active,
                                                   const int32_t* __restrict__ nact,
                                                   double* __restrict__ g) {
-    const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int j = blockIdx.x * 4 + wave_id();
     const int lane = threadIdx.x & 63;
     if (j >= S) return;
     double s = 0.0;
@@ -773,7 +773,7 @@ __global__ __launch_bounds__(256) void k_omp_fit(int n, const double* __restrict
 
 __global__ __launch_bounds__(256) void k_row_norm(int S, int ldz, const double* __restrict__ Z, int n,
                                                   double* __restrict__ nrm) {
-    const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int j = blockIdx.x * 4 + wave_id();
     const int lane = threadIdx.x & 63;
     if (j >= S) return;
     double s = 0.0;

@@ -140,7 +140,7 @@ __device__ __forceinline__ void d_mat_stats(int n, int ldn, int c0, int c1,
                                                    double* __restrict__ Cf, double* __restrict__ mu,
                                                    double* __restrict__ mur, double* __restrict__ msq,
                                                    uint8_t* __restrict__ valid) {
-    const int c = c0 + blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int c = c0 + blockIdx.x * 4 + wave_id();
     const int lane = threadIdx.x & 63;
     if (c >= c1) return;
     const double* v = Vf + (int64_t)c * ldn;
@@ -393,7 +393,7 @@ __device__ __forceinline__ void d_score_list(const ListItem* __restrict__ items,
                                                     unsigned long long* __restrict__ nscored,
                                                     uint8_t* __restrict__ r2v, double* __restrict__ r2m,
                                                     double* __restrict__ r2q, int64_t off2, int64_t off3) {
-    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t w = (int64_t)blockIdx.x * 4 + wave_id();
     if (w >= m) return;
     const ListItem it = items[w];
     Cand c{it.kind, it.op, it.ca, it.cb, OP_NONE, -1, -1};
@@ -738,11 +738,19 @@ __device__ __forceinline__ bool dev_unit_rule(int op, int B, const int32_t* ua, 
     }
 }
 
+constexpr int R3_SB = 2;              // samples regenerated ahead of their accumulation
+
+// Read-only operand arrays of the rung-3 kernel, read through the constant
+// address space: the kernel never writes them, so wave-uniform loads (the
+// primary operand, the targets, a binary tile's common operand) become
+// scalar loads even though the kernel stores scores between its loops.
+typedef const __attribute__((address_space(4))) double r3c_double;
+
 template <int OPS, int IC, int TP>
 __global__ __launch_bounds__(256) void k_screen_r3(R3Args g) {
     constexpr int NOP = ((OPS >> 0) & 1) + ((OPS >> 1) & 1) + ((OPS >> 2) & 1) +
                         ((OPS >> 3) & 1) + ((OPS >> 4) & 1);
-    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t w = (int64_t)blockIdx.x * 4 + wave_id();
     if (w >= g.n_tiles) return;
     const int lane = threadIdx.x & 63;
     const int4 tile = g.tiles[w];
@@ -813,39 +821,49 @@ __global__ __launch_bounds__(256) void k_screen_r3(R3Args g) {
             for (int q = 0; q < NOP; q++)
 #pragma unroll
                 for (int v = 0; v < 2 + TP; v++) acc[ii][q][v] = 0.0;
-        for (int s = 0; s < nn_i; s++) {
-            double f2;
+        r3c_double* __restrict__ Vs = (r3c_double*)g.Vs;
+        r3c_double* __restrict__ Rs = (r3c_double*)g.Rs;
+        r3c_double* __restrict__ Vf = (r3c_double*)g.Vf;
+        r3c_double* __restrict__ Rf = (r3c_double*)g.Rf;
+        r3c_double* __restrict__ Cf = (r3c_double*)g.Cf;
+        r3c_double* __restrict__ Yn = (r3c_double*)g.Yn;
+        // regenerated rung-2 value of sample s (uniform branches on the tile)
+        auto regen = [&](int s, double& f2, double& rf2) {
             if (tile.w == -2) {
                 const int64_t so = (int64_t)s * g.ldm + lc;
-                const double a = g.Vs[so];
-                f2 = op2 == OP_INV ? g.Rs[so] : op2 == OP_SQ ? a * a : apply_op(op2, a, 0.0);
+                const double a = Vs[so];
+                f2 = op2 == OP_INV ? Rs[so] : op2 == OP_SQ ? a * a : apply_op(op2, a, 0.0);
             } else {
-                const double a = g.Vs[(int64_t)s * g.ldm + kc];
-                const double b = g.Vf[(int64_t)lc * g.ldn + s];
+                // binary op2: the second operand l is the same for the whole wave
+                const double a = Vs[(int64_t)s * g.ldm + kc];
+                const double b = Vf[(int64_t)tile.y * g.ldn + s];
                 switch (op2) {
                 case OP_ADD: f2 = a + b; break;
                 case OP_SUB: f2 = a - b; break;
                 case OP_MUL: f2 = a * b; break;
-                case OP_DIV: f2 = a * g.Rf[(int64_t)lc * g.ldn + s]; break;
-                default: f2 = b * g.Rs[(int64_t)s * g.ldm + kc]; break;
+                case OP_DIV: f2 = a * Rf[(int64_t)tile.y * g.ldn + s]; break;
+                default: f2 = b * Rs[(int64_t)s * g.ldm + kc]; break;
                 }
             }
-            const double f2c = f2 - mu2;
-            double rf2 = 0.0;
+            rf2 = 0.0;
             if (want_rcp) {
                 double r = __builtin_amdgcn_rcp(f2);
                 r = fma(r, fma(-f2, r, 1.0), r);
                 rf2 = fma(r, fma(-f2, r, 1.0), r);
             }
+        };
+        // moments of sample s (straight-line)
+        auto accum = [&](int s, double f2, double rf2) {
+            const double f2c = f2 - mu2;
             double y[TP];
 #pragma unroll
-            for (int t = 0; t < TP; t++) y[t] = g.Yn[(int64_t)t * g.ldn + s];
+            for (int t = 0; t < TP; t++) y[t] = Yn[(int64_t)t * g.ldn + s];
 #pragma unroll
             for (int ii = 0; ii < IC; ii++) {
                 const int i = min(i0 + ii, g.pe - 1);
-                const double x = g.Vf[(int64_t)i * g.ldn + s];
-                const double xc = (OPS & 3) ? g.Cf[(int64_t)i * g.ldn + s] : 0.0;
-                const double rx = (OPS & 16) ? g.Rf[(int64_t)i * g.ldn + s] : 0.0;
+                const double x = Vf[(int64_t)i * g.ldn + s];
+                const double xc = (OPS & 3) ? Cf[(int64_t)i * g.ldn + s] : 0.0;
+                const double rx = (OPS & 16) ? Rf[(int64_t)i * g.ldn + s] : 0.0;
                 double f[NOP];
                 int q = 0;
                 if (OPS & 1) { f[q] = xc + f2c; q++; }
@@ -862,6 +880,21 @@ __global__ __launch_bounds__(256) void k_screen_r3(R3Args g) {
                     for (int t = 0; t < TP; t++) acc[ii][qq][2 + t] = fma(f[qq], y[t], acc[ii][qq][2 + t]);
                 }
             }
+        };
+        // samples in groups of R3_SB: the branchy regeneration first, then the
+        // straight-line accumulation (same order of every sum as one at a time)
+        int s = 0;
+        for (; s + R3_SB <= nn_i; s += R3_SB) {
+            double f2v[R3_SB], rf2v[R3_SB];
+#pragma unroll
+            for (int u = 0; u < R3_SB; u++) regen(s + u, f2v[u], rf2v[u]);
+#pragma unroll
+            for (int u = 0; u < R3_SB; u++) accum(s + u, f2v[u], rf2v[u]);
+        }
+        for (; s < nn_i; s++) {
+            double f2, rf2;
+            regen(s, f2, rf2);
+            accum(s, f2, rf2);
         }
         // finalise the IC x NOP candidates of this chunk
 #pragma unroll
@@ -993,7 +1026,7 @@ __global__ __launch_bounds__(256) void k_screen_lp(PairArgs g, const void* __res
     typedef typename LpVec<FP16>::T VT;
     typedef typename std::conditional<FP16, _Float16, __bf16>::type ET;
     const ET* __restrict__ Ylp = (const ET*)Ylp_;
-    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t w = (int64_t)blockIdx.x * 4 + wave_id();
     if (w >= g.n_tiles) return;
     const int lane = threadIdx.x & 63;
     const int col = lane & 15, kb = lane >> 4;
@@ -1198,7 +1231,7 @@ __device__ __forceinline__ void d_rescore(const int64_t* __restrict__ pool,
                                                  unsigned long long* __restrict__ maxerr) {
     const int64_t P = min((int64_t)*Pp, cap);
     const int lane = threadIdx.x & 63;
-    for (int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); w < P; w += (int64_t)gridDim.x * 4) {
+    for (int64_t w = (int64_t)blockIdx.x * 4 + wave_id(); w < P; w += (int64_t)gridDim.x * 4) {
     const int64_t id = pool[w];
     Cand c;
     bool ok = cand_of_id(ev, id, c);
@@ -1240,7 +1273,7 @@ __device__ __forceinline__ void d_fixup(const int64_t* __restrict__ ids,
                                                uint8_t* __restrict__ r2v, double* __restrict__ r2m,
                                                double* __restrict__ r2q) {
     const int64_t m = min((int64_t)*cnt, cap);
-    for (int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); w < m; w += (int64_t)gridDim.x * 4) {
+    for (int64_t w = (int64_t)blockIdx.x * 4 + wave_id(); w < m; w += (int64_t)gridDim.x * 4) {
         const int64_t id = ids[w];
         Cand c;
         bool ok = cand_of_id(ev, id, c);
@@ -1351,7 +1384,7 @@ __device__ __forceinline__ void d_pairs(const int64_t* __restrict__ pool,
     const int64_t P = min((int64_t)*Pp, cap);
     const int64_t total = min(off[P], flag_cap);
     const int lane = threadIdx.x & 63;
-    for (int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); w < total;
+    for (int64_t w = (int64_t)blockIdx.x * 4 + wave_id(); w < total;
          w += (int64_t)gridDim.x * 4) {
     // find q with off[q] <= w < off[q+1]
     int64_t a = 0, b = P;
@@ -1596,7 +1629,7 @@ __device__ __forceinline__ void d_bitonic(const double* __restrict__ ps,
 __device__ __forceinline__ void d_values(const int64_t* __restrict__ ids, int64_t m,
                                                 const EvalCtx& ev, Ops o, int n,
                                                 double* __restrict__ out, int64_t ldv) {
-    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t w = (int64_t)blockIdx.x * 4 + wave_id();
     if (w >= m) return;
     const int lane = threadIdx.x & 63;
     const int64_t id = ids[w];
