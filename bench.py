@@ -240,6 +240,34 @@ def large_main(args):
                 kern[kn] = {"launches_per_step": n / args.steps, "ms_per_step": t / args.steps}
         res[name] = (dt, out, kern)
         print("large24 %s: %.1f ms per step" % (name, dt * 1e3), file=sys.stderr, flush=True)
+    # the precision form on its own, at these shapes: the rung-2 space of the
+    # 24 features (5,810,274 raw candidates) screened against T = 8 and 16
+    # targets (max score, top-1000), FP64 vs BF16 vs FP16
+    rng = np.random.default_rng(8)
+    Xs = torch.as_tensor(w["X"], device=dev)
+    prec = {}
+    for T in (8, 16):
+        Y = torch.as_tensor(w["Y"][0][None, :] + 0.3 * rng.normal(size=(T, w["n"])) *
+                            np.std(w["Y"][0]), device=dev)
+        times, sel = {}, {}
+        for name, pr in (("fp64", Dm.FP64), ("bf16", Dm.BF16_GUARD), ("fp16", Dm.FP16_GUARD)):
+            prm = Dm.params(ops=w["ops"], rung=2, k=w["k"], score_mode=Dm.SCORE_MAX, precision=pr)
+            for _ in range(max(1, args.warmup)):
+                ids, sc, _, st = ctx.generate_screen(Xs, Y, prm, units=w["units"], values=False)
+            torch.cuda.synchronize()
+            reps = max(3, args.steps)
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                ids, sc, _, st = ctx.generate_screen(Xs, Y, prm, units=w["units"], values=False)
+            torch.cuda.synchronize()
+            times[name] = (time.perf_counter() - t0) / reps * 1e3
+            sel[name] = ids.cpu().numpy()
+        prec["T%d" % T] = {"ms_fp64": times["fp64"], "ms_bf16": times["bf16"], "ms_fp16": times["fp16"],
+                           "speedup_bf16": times["fp64"] / times["bf16"],
+                           "speedup_fp16": times["fp64"] / times["fp16"],
+                           "identical": bool(np.array_equal(sel["fp64"], sel["bf16"]) and
+                                             np.array_equal(sel["fp64"], sel["fp16"]))}
+        print("precision rung 2, T=%d: %s" % (T, prec["T%d" % T]), file=sys.stderr, flush=True)
     dt, out, kern = res["bf16"]
     screened = sum(d["screen_stats"]["n_unit_valid"] for d in out["dims"])
     subsets = sum(d["l0_stats"]["n_subsets"] for d in out["dims"])
@@ -281,6 +309,7 @@ def large_main(args):
         "speedup_bf16_vs_fp64": res["fp64"][0] / res["bf16"][0],
         "speedup_fp16_vs_fp64": res["fp64"][0] / res["fp16"][0],
         "identical_selections": bool(same), "max_lowprec_err": err, "guard_band": band,
+        "precision_form_rung2": prec,
         "kernels_bf16": kern, "kernels_fp64": res["fp64"][2], "roofline": roof,
     }
     if not same:

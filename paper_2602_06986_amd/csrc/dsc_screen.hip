@@ -981,10 +981,10 @@ __global__ __launch_bounds__(256) void k_screen_r3(R3Args g) {
 // |r_lp - r| <= 2u + u^2 + gamma_n(FP32) (+2^-24 for FP16 subnormals), with
 // u = 2^-8 (BF16) or 2^-11 (FP16); every candidate within 2 delta of the
 // pool threshold is rescored in FP64.
-constexpr int LP_IB = 1;
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8_t;
 typedef __attribute__((ext_vector_type(8))) _Float16 f16x8_t;
 typedef __attribute__((ext_vector_type(4))) float f32x4_t;
+typedef __attribute__((ext_vector_type(8))) float f32x8_t;
 
 template <bool FP16>
 struct LpVec;
@@ -1017,179 +1017,233 @@ __global__ void k_targets_lp(int n, int T, int ldn, int ldl, const double* __res
     Ylp[(int64_t)t * ldl + s] = LpVec<FP16>::cvt((float)v);
 }
 
+// Layout of the kernel: one block (4 waves) = 64 operand features i (one
+// per lane) x one operand feature j; the waves split the samples into
+// 32-sample chunks.  Pass 1 gives the FP64 shifted moments as in the FP64
+// kernel, summed over the waves in LDS in a fixed order.  Pass 2: each lane
+// forms z for its candidate at a chunk's samples, rounds it and stores it in
+// its wave's LDS area with the candidate's 32 values contiguous; the MFMA B
+// operand of lane l (candidate 16g + l%16, samples 8(l/16)..+7) is then one
+// 16-byte LDS read, and one MFMA per (operator, group of 16 candidates)
+// accumulates the chunk.  The waves' FP32 products are summed in LDS in a
+// fixed order; wave w then writes the scores of candidates 16w..16w+15.
+constexpr int LPT_CH = 32;                 // samples per MFMA chunk
+
 template <int OPS, bool FP16>
 __global__ __launch_bounds__(256) void k_screen_lp(PairArgs g, const void* __restrict__ Ylp_, int ldl) {
     constexpr int NOP = ((OPS >> 0) & 1) + ((OPS >> 1) & 1) + ((OPS >> 2) & 1) +
                         ((OPS >> 3) & 1) + ((OPS >> 4) & 1);
-    constexpr int IB = LP_IB;                              // LP_IB x 16 operand features i per wave
-    constexpr int G = IB * NOP;
     typedef typename LpVec<FP16>::T VT;
     typedef typename std::conditional<FP16, _Float16, __bf16>::type ET;
+    __shared__ __align__(16) ET zs[4][NOP][64][LPT_CH];    // also the combine buffers
+    __shared__ double okf[NOP][64][3];     // per candidate: flag, mean, variance
     const ET* __restrict__ Ylp = (const ET*)Ylp_;
-    const int64_t w = (int64_t)blockIdx.x * 4 + wave_id();
-    if (w >= g.n_tiles) return;
+    const int2 tile = g.tiles[blockIdx.x];
+    const int wave = wave_id();
     const int lane = threadIdx.x & 63;
-    const int col = lane & 15, kb = lane >> 4;
-    const int2 tile = g.tiles[w];
     const int jc = tile.x;                                 // one j per tile
+    const int i = tile.y + lane;
+    const bool iok = i < g.i_end && i < jc;
+    const int ic = i < g.Mc ? i : 0;
     const double mub = g.mu[jc], murb = g.mur[jc];
-    int ic[IB];
-    bool iok[IB];
-    double sh[IB][NOP];
-#pragma unroll
-    for (int b = 0; b < IB; b++) {
-        const int i = tile.y + 16 * b + col;
-        iok[b] = i < g.i_end && i < jc;
-        ic[b] = i < g.Mc ? i : 0;
-        const double mua = g.mu[ic[b]], mura = g.mur[ic[b]];
+    const double mua = g.mu[ic], mura = g.mur[ic];
+    double sh[NOP];
+    {
         int k = 0;
-        if (OPS & 1) sh[b][k++] = 0.0;
-        if (OPS & 2) sh[b][k++] = 0.0;
-        if (OPS & 4) sh[b][k++] = mua * mub;
-        if (OPS & 8) sh[b][k++] = mua * murb;
-        if (OPS & 16) sh[b][k++] = mura * mub;
+        if (OPS & 1) sh[k++] = 0.0;
+        if (OPS & 2) sh[k++] = 0.0;
+        if (OPS & 4) sh[k++] = mua * mub;
+        if (OPS & 8) sh[k++] = mua * murb;
+        if (OPS & 16) sh[k++] = mura * mub;
     }
-    auto values = [&](int s, double f[IB][NOP]) {
+    auto values = [&](int s, double f[NOP]) {
         const double b_ = g.Vf[(int64_t)jc * g.ldn + s];
         const double rb = g.Rf[(int64_t)jc * g.ldn + s];
         const double bc = g.Cf[(int64_t)jc * g.ldn + s];
-#pragma unroll
-        for (int b = 0; b < IB; b++) {
-            const int64_t so = (int64_t)s * g.ldm + ic[b];
-            const double a = g.Vs[so], ra = g.Rs[so], ac = g.Cs[so];
-            int k = 0;
-            if (OPS & 1) { f[b][k] = ac + bc; k++; }
-            if (OPS & 2) { f[b][k] = ac - bc; k++; }
-            if (OPS & 4) { f[b][k] = fma(a, b_, -sh[b][k]); k++; }
-            if (OPS & 8) { f[b][k] = fma(a, rb, -sh[b][k]); k++; }
-            if (OPS & 16) { f[b][k] = fma(ra, b_, -sh[b][k]); k++; }
-        }
+        const int64_t so = (int64_t)s * g.ldm + ic;
+        const double a = g.Vs[so], ra = g.Rs[so], ac = g.Cs[so];
+        int k = 0;
+        if (OPS & 1) { f[k] = ac + bc; k++; }
+        if (OPS & 2) { f[k] = ac - bc; k++; }
+        if (OPS & 4) { f[k] = fma(a, b_, -sh[k]); k++; }
+        if (OPS & 8) { f[k] = fma(a, rb, -sh[k]); k++; }
+        if (OPS & 16) { f[k] = fma(ra, b_, -sh[k]); k++; }
     };
-    // pass 1: shifted moments over this lane's samples, then across the 4
-    // lanes that share a candidate
-    double s1[G], s2[G];
+    const int nch = (g.n + LPT_CH - 1) / LPT_CH;
+    const int cpw = (nch + 3) / 4;                         // chunks per wave
+    const int c0 = wave * cpw, c1 = min(nch, c0 + cpw);
+    // pass 1: shifted moments over this wave's samples, summed over the waves
+    double s1[NOP], s2[NOP];
 #pragma unroll
-    for (int q = 0; q < G; q++) { s1[q] = 0.0; s2[q] = 0.0; }
-    const int nch = (g.n + 31) / 32;
-    for (int c = 0; c < nch; c++) {
-        for (int e = 0; e < 8; e++) {
-            const int s = 32 * c + 8 * kb + e;
-            if (s >= g.n) break;
-            double f[IB][NOP];
-            values(s, f);
+    for (int q = 0; q < NOP; q++) { s1[q] = 0.0; s2[q] = 0.0; }
+    const int s_hi = min(g.n, c1 * LPT_CH);
+#pragma unroll 2
+    for (int s = min(g.n, c0 * LPT_CH); s < s_hi; s++) {
+        double f[NOP];
+        values(s, f);
 #pragma unroll
-            for (int b = 0; b < IB; b++)
-#pragma unroll
-                for (int k = 0; k < NOP; k++) {
-                    s1[b * NOP + k] += f[b][k];
-                    s2[b * NOP + k] = fma(f[b][k], f[b][k], s2[b * NOP + k]);
-                }
+        for (int q = 0; q < NOP; q++) {
+            s1[q] += f[q];
+            s2[q] = fma(f[q], f[q], s2[q]);
         }
     }
+    {
+        double* red = (double*)&zs[0][0][0][0];             // [4][NOP][2][64]
 #pragma unroll
-    for (int q = 0; q < G; q++) {
-        // fixed order: (kb0 + kb1) + (kb2 + kb3) in every lane
-        const double a1 = s1[q] + __shfl_xor(s1[q], 16, 64);
-        s1[q] = a1 + __shfl_xor(a1, 32, 64);
-        const double a2 = s2[q] + __shfl_xor(s2[q], 16, 64);
-        s2[q] = a2 + __shfl_xor(a2, 32, 64);
+        for (int q = 0; q < NOP; q++) {
+            red[((wave * NOP + q) * 2 + 0) * 64 + lane] = s1[q];
+            red[((wave * NOP + q) * 2 + 1) * 64 + lane] = s2[q];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < NOP; q++) {
+            const double* r1 = red + (q * 2 + 0) * 64 + lane;
+            const double* r2 = red + (q * 2 + 1) * 64 + lane;
+            const int ws = NOP * 2 * 64;                   // stride between waves
+            s1[q] = (r1[0] + r1[ws]) + (r1[2 * ws] + r1[3 * ws]);
+            s2[q] = (r2[0] + r2[ws]) + (r2[2 * ws] + r2[3 * ws]);
+        }
+        __syncthreads();
     }
     const double nn = (double)g.n;
-    double isd[G], cz[G];
-    unsigned okmask = 0, fixmask = 0;
+    double isd[NOP], cz[NOP];
 #pragma unroll
-    for (int b = 0; b < IB; b++)
-#pragma unroll
-        for (int k = 0; k < NOP; k++) {
-            const int q = b * NOP + k;
-            const double m1 = s1[q] / nn, varn = s2[q] - s1[q] * m1;
-            const bool fin = (s2[q] < INFINITY) && (fabs(s1[q]) < INFINITY);
-            double kappa = varn > 0.0 ? s2[q] / varn : INFINITY;
-            if ((OPS & 3) && k < ((OPS & 1) + ((OPS >> 1) & 1))) {   // add / sub
-                const bool isadd = (OPS & 1) && k == 0;
-                const double c0 = isadd ? g.mu[ic[b]] + mub : g.mu[ic[b]] - mub;
-                const double ff = s2[q] + 2.0 * c0 * s1[q] + nn * c0 * c0;
-                if (ff <= 1e-12 * nn * (g.msq[ic[b]] + g.msq[jc])) kappa = INFINITY;
-            }
-            bool ok = iok[b] && g.valid[ic[b]] && g.valid[jc] && fin;
-            if (ok && !(kappa <= KAPPA_MAX)) { fixmask |= 1u << q; ok = false; }
-            isd[q] = ok ? sqrt(nn / varn) : 0.0;           // 1 / population sd
-            cz[q] = m1 * isd[q];
-            if (ok) okmask |= 1u << q;
+    for (int q = 0; q < NOP; q++) {
+        const double m1 = s1[q] / nn, varn = s2[q] - s1[q] * m1;
+        const bool fin = (s2[q] < INFINITY) && (fabs(s1[q]) < INFINITY);
+        double kappa = varn > 0.0 ? s2[q] / varn : INFINITY;
+        if ((OPS & 3) && q < ((OPS & 1) + ((OPS >> 1) & 1))) {   // add / sub
+            const bool isadd = (OPS & 1) && q == 0;
+            const double c0_ = isadd ? mua + mub : mua - mub;
+            const double ff = s2[q] + 2.0 * c0_ * s1[q] + nn * c0_ * c0_;
+            if (ff <= 1e-12 * nn * (g.msq[ic] + g.msq[jc])) kappa = INFINITY;
         }
-    // pass 2: low-precision products on the matrix cores
-    f32x4_t acc[G];
-#pragma unroll
-    for (int q = 0; q < G; q++) acc[q] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-    for (int c = 0; c < nch; c++) {
-        const VT ya = *(const VT*)(Ylp + (int64_t)col * ldl + 32 * c + 8 * kb);
-        VT bv[G];
-#pragma unroll
-        for (int e = 0; e < 8; e++) {
-            const int s = 32 * c + 8 * kb + e;
-            double f[IB][NOP];
-            if (s < g.n) values(s, f);
-#pragma unroll
-            for (int q = 0; q < G; q++) {
-                const double z = s < g.n ? fma(f[q / NOP][q % NOP], isd[q], -cz[q]) : 0.0;
-                bv[q][e] = LpVec<FP16>::cvt((float)z);
-            }
+        bool ok = iok && g.valid[ic] && g.valid[jc] && fin;
+        const bool fix = ok && !(kappa <= KAPPA_MAX);
+        ok = ok && !fix;
+        isd[q] = ok ? sqrt(nn / varn) : 0.0;               // 1 / population sd
+        cz[q] = m1 * isd[q];
+        if (wave == 0) {
+            okf[q][lane][0] = ok ? 1.0 : fix ? 2.0 : 0.0;
+            okf[q][lane][1] = sh[q] + m1;
+            okf[q][lane][2] = varn / nn;
         }
-#pragma unroll
-        for (int q = 0; q < G; q++) acc[q] = LpVec<FP16>::mma(ya, bv[q], acc[q]);
     }
-    // scores: lane holds r for targets 4kb..4kb+3 of candidate col
+    // pass 2: low-precision products on the matrix cores
+    f32x4_t acc[NOP][4];
+#pragma unroll
+    for (int q = 0; q < NOP; q++)
+#pragma unroll
+        for (int gq = 0; gq < 4; gq++) acc[q][gq] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    const int col = lane & 15, kb = lane >> 4;
+    for (int c = c0; c < c0 + cpw; c++) {                  // every wave runs cpw chunks
+        if (c < c1) {
+            // 8 samples at a time: each operator's 8 rounded values leave in
+            // one 16-byte LDS write
+            for (int e0 = 0; e0 < LPT_CH; e0 += 8) {
+                f32x8_t zf[NOP];
+#pragma unroll
+                for (int u = 0; u < 8; u++) {
+                    const int s = c * LPT_CH + e0 + u;
+                    double f[NOP];
+                    if (s < g.n) values(s, f);
+#pragma unroll
+                    for (int q = 0; q < NOP; q++)
+                        zf[q][u] = s < g.n ? (float)fma(f[q], isd[q], -cz[q]) : 0.f;
+                }
+#pragma unroll
+                for (int q = 0; q < NOP; q++)
+                    *(VT*)&zs[wave][q][lane][e0] = __builtin_convertvector(zf[q], VT);
+            }
+        }
+        __syncthreads();                                   // chunk written
+        if (c < c1) {
+            const VT ya = *(const VT*)(Ylp + (int64_t)col * ldl + LPT_CH * c + 8 * kb);
+#pragma unroll
+            for (int q = 0; q < NOP; q++)
+#pragma unroll
+                for (int gq = 0; gq < 4; gq++) {
+                    const VT bv = *(const VT*)&zs[wave][q][16 * gq + col][8 * kb];
+                    acc[q][gq] = LpVec<FP16>::mma(ya, bv, acc[q][gq]);
+                }
+        }
+        __syncthreads();                                   // reads done before the next chunk
+    }
+    // sum the products of the 4 waves (fixed order); wave w keeps group w
+    float* red = (float*)&zs[0][0][0][0];                  // [4 waves][NOP][4 groups][4][64]
+#pragma unroll
+    for (int q = 0; q < NOP; q++)
+#pragma unroll
+        for (int gq = 0; gq < 4; gq++)
+#pragma unroll
+            for (int e = 0; e < 4; e++)
+                red[(((wave * NOP + q) * 4 + gq) * 4 + e) * 64 + lane] = acc[q][gq][e];
+    __syncthreads();
+    const int gq = wave;
+    float rs[NOP][4];
+#pragma unroll
+    for (int q = 0; q < NOP; q++)
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            float x[4];
+#pragma unroll
+            for (int w2 = 0; w2 < 4; w2++) x[w2] = red[(((w2 * NOP + q) * 4 + gq) * 4 + e) * 64 + lane];
+            rs[q][e] = (x[0] + x[1]) + (x[2] + x[3]);
+        }
+    // scores: lane holds r for targets 4kb..4kb+3 of candidate 16gq + col
     unsigned cnt = 0;
+    const int cl = 16 * gq + col;
+    const int ii = tile.y + cl;
+    const bool cok = ii < g.i_end && ii < jc;
+    const int icl = ii < g.Mc ? ii : 0;
+    int k = 0;
 #pragma unroll
-    for (int b = 0; b < IB; b++) {
-        const int i = tile.y + 16 * b + col;
-        int k = 0;
+    for (int o = 0; o < 5; o++) {
+        if (!((OPS >> o) & 1)) continue;
+        const int q = k++;
+        double r[4];
+        double mx = 0.0;
 #pragma unroll
-        for (int o = 0; o < 5; o++) {
-            if (!((OPS >> o) & 1)) continue;
-            const int q = b * NOP + k++;
-            double r[4];
-            double mx = 0.0;
-#pragma unroll
-            for (int e = 0; e < 4; e++) {
-                r[e] = fabs((double)acc[q][e]) / nn;
-                if (4 * kb + e < g.T) mx = fmax(mx, r[e]);
+        for (int e = 0; e < 4; e++) {
+            r[e] = fabs((double)rs[q][e]) / nn;
+            if (4 * kb + e < g.T) mx = fmax(mx, r[e]);
+        }
+        mx = fmax(mx, __shfl_xor(mx, 16, 64));
+        mx = fmax(mx, __shfl_xor(mx, 32, 64));
+        if (!cok || !((g.opmask >> o) & 1)) continue;
+        const int64_t id = pair_id(g.sd, g.r, OP_ADD + o, g.mat_raw[icl], g.mat_raw[jc]);
+        const double nanv = __longlong_as_double(-1LL);
+        const double flag = okf[q][cl][0];
+        const bool ok = flag == 1.0;
+        if (flag == 2.0) {
+            if (kb == 0) {
+                const unsigned long long slot = atomicAdd(g.fix_cnt, 1ull);
+                if ((int64_t)slot < g.fix_cap) g.fix_ids[slot] = id;
+                if (g.mode == DISCOVER_SCORE_MAX) g.scores[id] = nanv;
             }
-            mx = fmax(mx, __shfl_xor(mx, 16, 64));
-            mx = fmax(mx, __shfl_xor(mx, 32, 64));
-            if (!iok[b] || !((g.opmask >> o) & 1)) continue;
-            const int64_t id = pair_id(g.sd, g.r, OP_ADD + o, g.mat_raw[ic[b]], g.mat_raw[jc]);
-            const double nanv = __longlong_as_double(-1LL);
-            const bool ok = (okmask >> q) & 1;
-            if ((fixmask >> q) & 1) {
-                if (kb == 0) {
-                    const unsigned long long slot = atomicAdd(g.fix_cnt, 1ull);
-                    if ((int64_t)slot < g.fix_cap) g.fix_ids[slot] = id;
-                    if (g.mode == DISCOVER_SCORE_MAX) g.scores[id] = nanv;
-                }
-                if (g.mode != DISCOVER_SCORE_MAX)
-                    for (int e = 0; e < 4; e++)
-                        if (4 * kb + e < g.T) g.scores[(int64_t)(4 * kb + e) * g.N + id] = nanv;
-                continue;
-            }
-            if (g.r2v && ok && kb == 0) {
-                const double sh_ = (o == 0) ? g.mu[ic[b]] + mub : (o == 1) ? g.mu[ic[b]] - mub : sh[b][k - 1];
-                const double mean_ = sh_ + s1[q] / nn;
-                const double var_ = (s2[q] - s1[q] * s1[q] / nn) / nn;
-                g.r2v[id - g.sd.off[2]] = 1;
-                g.r2m[id - g.sd.off[2]] = mean_;
-                g.r2q[id - g.sd.off[2]] = var_ + mean_ * mean_;
-            }
-            if (g.mode == DISCOVER_SCORE_MAX) {
-                if (kb == 0) {
-                    g.scores[id] = ok ? mx : nanv;
-                    cnt += ok;
-                }
-            } else {
+            if (g.mode != DISCOVER_SCORE_MAX)
                 for (int e = 0; e < 4; e++)
-                    if (4 * kb + e < g.T) g.scores[(int64_t)(4 * kb + e) * g.N + id] = ok ? r[e] : nanv;
-                if (kb == 0) cnt += ok;
+                    if (4 * kb + e < g.T) g.scores[(int64_t)(4 * kb + e) * g.N + id] = nanv;
+            continue;
+        }
+        if (g.r2v && ok && kb == 0) {
+            const double mua_ = g.mu[icl];
+            const double mean_ = o == 0 ? (mua_ + mub) + okf[q][cl][1]
+                               : o == 1 ? (mua_ - mub) + okf[q][cl][1] : okf[q][cl][1];
+            const double var_ = okf[q][cl][2];
+            g.r2v[id - g.sd.off[2]] = 1;
+            g.r2m[id - g.sd.off[2]] = mean_;
+            g.r2q[id - g.sd.off[2]] = var_ + mean_ * mean_;
+        }
+        if (g.mode == DISCOVER_SCORE_MAX) {
+            if (kb == 0) {
+                g.scores[id] = ok ? mx : nanv;
+                cnt += ok;
             }
+        } else {
+            for (int e = 0; e < 4; e++)
+                if (4 * kb + e < g.T) g.scores[(int64_t)(4 * kb + e) * g.N + id] = ok ? r[e] : nanv;
+            if (kb == 0) cnt += ok;
         }
     }
     for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor((int)cnt, o, 64);
@@ -1816,7 +1870,7 @@ static void launch_pairs(int OPS, ctab<PairArgs> A, const int4* tiles, int64_t n
 
 template <bool FP16>
 static void launch_lp(int cls, const PairArgs& a, const void* ylp, int ldl, hipStream_t st) {
-    const unsigned blocks = (unsigned)cdiv(a.n_tiles, 4);
+    const unsigned blocks = (unsigned)a.n_tiles;           // one block per (j, 64 i) tile
     if (!blocks) return;
     switch (cls) {
     case 31: k_screen_lp<31, FP16><<<blocks, 256, 0, st>>>(a, ylp, ldl); break;
@@ -1954,7 +2008,7 @@ static std::shared_ptr<Plan> get_plan(discover_ctx* ctx, const discover_problem&
         std::vector<int2> pt;
         for (int32_t j = jc0; j < jc1; j++) {
             const int32_t ilim = std::min<int32_t>(i_end, j);
-            for (int32_t i0 = 0; i0 < ilim; i0 += 16 * LP_IB) pt.push_back(make_int2(j, i0));
+            for (int32_t i0 = 0; i0 < ilim; i0 += 64) pt.push_back(make_int2(j, i0));
         }
         P->ptiles = P->up(pt);
         P->n_ptiles = (int64_t)pt.size();
