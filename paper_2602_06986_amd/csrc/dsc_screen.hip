@@ -985,6 +985,7 @@ typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8_t;
 typedef __attribute__((ext_vector_type(8))) _Float16 f16x8_t;
 typedef __attribute__((ext_vector_type(4))) float f32x4_t;
 typedef __attribute__((ext_vector_type(8))) float f32x8_t;
+typedef __attribute__((ext_vector_type(4))) __bf16 bf16x4_t;
 
 template <bool FP16>
 struct LpVec;
@@ -1243,6 +1244,237 @@ __global__ __launch_bounds__(256) void k_screen_lp(PairArgs g, const void* __res
         } else {
             for (int e = 0; e < 4; e++)
                 if (4 * kb + e < g.T) g.scores[(int64_t)(4 * kb + e) * g.N + id] = ok ? r[e] : nanv;
+            if (kb == 0) cnt += ok;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor((int)cnt, o, 64);
+    if (lane == 0 && cnt) atomicAdd(g.nscored, (unsigned long long)cnt);
+}
+
+// Single-pass BF16 form.  The Pearson numerator does not need the mean:
+// with centred targets, sum_s (f_s - c) y_s is the same for every constant
+// c.  So each lane rounds the shifted value u = f - shift (the FP64
+// kernel's shift estimate) to BF16 directly, while the same pass sums u and
+// u^2 in FP64 for the variance.  With y standardised (sum y^2 = n),
+// r = sum_s u_s y_s / sqrt(n var_n), and rounding u and y (and summing in
+// FP32) changes r by at most delta * sqrt(kappa), kappa = sum u^2 / var_n
+// (the same bound as for standardised values, scaled by the size of u
+// relative to its spread).  A candidate with kappa <= LP1_KAPPA stores its
+// score (error within the selection margin 2 delta); up to KAPPA_MAX it
+// stores the upper bound -(s + delta sqrt(kappa)) (rescored exactly when it
+// can reach the pool); beyond that it is decided by the FP64 fix-up pass.
+// BF16 keeps FP32's exponent range, so u needs no scaling.
+constexpr double LP1_KAPPA = 4.0;
+
+template <int OPS>
+__global__ __launch_bounds__(256) void k_screen_lp1(PairArgs g, const void* __restrict__ Ylp_, int ldl,
+                                                    double delta) {
+    constexpr int NOP = ((OPS >> 0) & 1) + ((OPS >> 1) & 1) + ((OPS >> 2) & 1) +
+                        ((OPS >> 3) & 1) + ((OPS >> 4) & 1);
+    typedef bf16x8_t VT;
+    __shared__ __align__(16) __bf16 zs[4][NOP][64][LPT_CH];    // also the combine buffers
+    __shared__ double cst[NOP][64][5];     // per candidate: state, 1/sqrt(n var), kappa, variance, mean shift
+    const __bf16* __restrict__ Ylp = (const __bf16*)Ylp_;
+    const int2 tile = g.tiles[blockIdx.x];
+    const int wave = wave_id();
+    const int lane = threadIdx.x & 63;
+    const int jc = tile.x;                                 // one j per tile
+    const int i = tile.y + lane;
+    const bool iok = i < g.i_end && i < jc;
+    const int ic = i < g.Mc ? i : 0;
+    const double mub = g.mu[jc], murb = g.mur[jc];
+    const double mua = g.mu[ic], mura = g.mur[ic];
+    double sh[NOP];
+    {
+        int k = 0;
+        if (OPS & 1) sh[k++] = 0.0;
+        if (OPS & 2) sh[k++] = 0.0;
+        if (OPS & 4) sh[k++] = mua * mub;
+        if (OPS & 8) sh[k++] = mua * murb;
+        if (OPS & 16) sh[k++] = mura * mub;
+    }
+    const int nch = (g.n + LPT_CH - 1) / LPT_CH;
+    const int cpw = (nch + 3) / 4;                         // chunks per wave
+    const int c0 = wave * cpw, c1 = min(nch, c0 + cpw);
+    double s1[NOP], s2[NOP];
+    f32x4_t acc[NOP][4];
+#pragma unroll
+    for (int q = 0; q < NOP; q++) {
+        s1[q] = 0.0;
+        s2[q] = 0.0;
+#pragma unroll
+        for (int gq = 0; gq < 4; gq++) acc[q][gq] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    }
+    const int col = lane & 15, kb = lane >> 4;
+    for (int c = c0; c < c0 + cpw; c++) {                  // every wave runs cpw chunks
+        if (c < c1) {
+            for (int e0 = 0; e0 < LPT_CH; e0 += 4) {
+                f32x4_t zf[NOP];
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    const int s = c * LPT_CH + e0 + u;
+                    double f[NOP];
+                    if (s < g.n) {
+                        const double b_ = g.Vf[(int64_t)jc * g.ldn + s];
+                        const double rb = g.Rf[(int64_t)jc * g.ldn + s];
+                        const double bc = g.Cf[(int64_t)jc * g.ldn + s];
+                        const int64_t so = (int64_t)s * g.ldm + ic;
+                        const double a = g.Vs[so], ra = g.Rs[so], ac = g.Cs[so];
+                        int k = 0;
+                        if (OPS & 1) { f[k] = ac + bc; k++; }
+                        if (OPS & 2) { f[k] = ac - bc; k++; }
+                        if (OPS & 4) { f[k] = fma(a, b_, -sh[k]); k++; }
+                        if (OPS & 8) { f[k] = fma(a, rb, -sh[k]); k++; }
+                        if (OPS & 16) { f[k] = fma(ra, b_, -sh[k]); k++; }
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < NOP; q++) f[q] = 0.0;
+                    }
+#pragma unroll
+                    for (int q = 0; q < NOP; q++) {
+                        s1[q] += f[q];
+                        s2[q] = fma(f[q], f[q], s2[q]);
+                        zf[q][u] = (float)f[q];
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < NOP; q++)
+                    *(bf16x4_t*)&zs[wave][q][lane][e0] = __builtin_convertvector(zf[q], bf16x4_t);
+            }
+        }
+        __syncthreads();                                   // chunk written
+        if (c < c1) {
+            const VT ya = *(const VT*)(Ylp + (int64_t)col * ldl + LPT_CH * c + 8 * kb);
+#pragma unroll
+            for (int q = 0; q < NOP; q++)
+#pragma unroll
+                for (int gq = 0; gq < 4; gq++) {
+                    const VT bv = *(const VT*)&zs[wave][q][16 * gq + col][8 * kb];
+                    acc[q][gq] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ya, bv, acc[q][gq], 0, 0, 0);
+                }
+        }
+        __syncthreads();                                   // reads done before the next chunk
+    }
+    const double nn = (double)g.n;
+    {
+        // moments over the waves: (w0 + w1) + (w2 + w3)
+        double* red = (double*)&zs[0][0][0][0];             // [4][NOP][2][64]
+#pragma unroll
+        for (int q = 0; q < NOP; q++) {
+            red[((wave * NOP + q) * 2 + 0) * 64 + lane] = s1[q];
+            red[((wave * NOP + q) * 2 + 1) * 64 + lane] = s2[q];
+        }
+        __syncthreads();
+        if (wave == 0) {
+            const int ws = NOP * 2 * 64;                   // stride between waves
+#pragma unroll
+            for (int q = 0; q < NOP; q++) {
+                const double* r1 = red + (q * 2 + 0) * 64 + lane;
+                const double* r2 = red + (q * 2 + 1) * 64 + lane;
+                const double S1 = (r1[0] + r1[ws]) + (r1[2 * ws] + r1[3 * ws]);
+                const double S2 = (r2[0] + r2[ws]) + (r2[2 * ws] + r2[3 * ws]);
+                const double m1 = S1 / nn, varn = S2 - S1 * m1;
+                const bool fin = (S2 < INFINITY) && (fabs(S1) < INFINITY);
+                double kappa = varn > 0.0 ? S2 / varn : INFINITY;
+                if ((OPS & 3) && q < ((OPS & 1) + ((OPS >> 1) & 1))) {   // add / sub
+                    const bool isadd = (OPS & 1) && q == 0;
+                    const double c0_ = isadd ? mua + mub : mua - mub;
+                    const double ff = S2 + 2.0 * c0_ * S1 + nn * c0_ * c0_;
+                    if (ff <= 1e-12 * nn * (g.msq[ic] + g.msq[jc])) kappa = INFINITY;
+                }
+                const bool ok = iok && g.valid[ic] && g.valid[jc] && fin;
+                double shq = sh[q];
+                if ((OPS & 1) && q == 0) shq = mua + mub;
+                if ((OPS & 2) && q == (OPS & 1)) shq = mua - mub;
+                const double mean = shq + m1;
+                const bool nonconst = varn / nn > TAU_CONST * TAU_CONST * (varn / nn + mean * mean);
+                // state: 0 invalid / constant, 1 precise, 2 upper bound, 3 fix-up
+                double state = 0.0;
+                if (ok && !(kappa <= KAPPA_MAX)) state = 3.0;
+                else if (ok && nonconst) state = kappa <= LP1_KAPPA ? 1.0 : 2.0;
+                cst[q][lane][0] = state;
+                cst[q][lane][1] = state == 1.0 || state == 2.0 ? 1.0 / sqrt(nn * varn) : 0.0;
+                cst[q][lane][2] = kappa;
+                cst[q][lane][3] = varn / nn;
+                cst[q][lane][4] = mean;
+            }
+        }
+        __syncthreads();
+    }
+    // products over the waves (fixed order); wave w keeps group w
+    float* fred = (float*)&zs[0][0][0][0];                 // [4 waves][NOP][4 groups][4][64]
+#pragma unroll
+    for (int q = 0; q < NOP; q++)
+#pragma unroll
+        for (int gq = 0; gq < 4; gq++)
+#pragma unroll
+            for (int e = 0; e < 4; e++)
+                fred[(((wave * NOP + q) * 4 + gq) * 4 + e) * 64 + lane] = acc[q][gq][e];
+    __syncthreads();
+    const int gq = wave;
+    float rs[NOP][4];
+#pragma unroll
+    for (int q = 0; q < NOP; q++)
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            float x[4];
+#pragma unroll
+            for (int w2 = 0; w2 < 4; w2++) x[w2] = fred[(((w2 * NOP + q) * 4 + gq) * 4 + e) * 64 + lane];
+            rs[q][e] = (x[0] + x[1]) + (x[2] + x[3]);
+        }
+    // scores: lane holds the products for targets 4kb..4kb+3 of candidate 16gq + col
+    unsigned cnt = 0;
+    const int cl = 16 * gq + col;
+    const int ii = tile.y + cl;
+    const bool cok = ii < g.i_end && ii < jc;
+    const int icl = ii < g.Mc ? ii : 0;
+    int k = 0;
+#pragma unroll
+    for (int o = 0; o < 5; o++) {
+        if (!((OPS >> o) & 1)) continue;
+        const int q = k++;
+        const double state = cst[q][cl][0], inv = cst[q][cl][1], kappa = cst[q][cl][2];
+        double r[4];
+        double mx = 0.0;
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            r[e] = fabs((double)rs[q][e]) * inv;
+            if (4 * kb + e < g.T) mx = fmax(mx, r[e]);
+        }
+        mx = fmax(mx, __shfl_xor(mx, 16, 64));
+        mx = fmax(mx, __shfl_xor(mx, 32, 64));
+        if (!cok || !((g.opmask >> o) & 1)) continue;
+        const int64_t id = pair_id(g.sd, g.r, OP_ADD + o, g.mat_raw[icl], g.mat_raw[jc]);
+        const double nanv = __longlong_as_double(-1LL);
+        if (state == 3.0) {
+            if (kb == 0) {
+                const unsigned long long slot = atomicAdd(g.fix_cnt, 1ull);
+                if ((int64_t)slot < g.fix_cap) g.fix_ids[slot] = id;
+                if (g.mode == DISCOVER_SCORE_MAX) g.scores[id] = nanv;
+            }
+            if (g.mode != DISCOVER_SCORE_MAX)
+                for (int e = 0; e < 4; e++)
+                    if (4 * kb + e < g.T) g.scores[(int64_t)(4 * kb + e) * g.N + id] = nanv;
+            continue;
+        }
+        const bool ok = state == 1.0 || state == 2.0;
+        const double ub = delta * sqrt(kappa);             // this candidate's error bound
+        if (g.r2v && ok && kb == 0) {
+            const double mean_ = cst[q][cl][4];
+            const double var_ = cst[q][cl][3];
+            g.r2v[id - g.sd.off[2]] = 1;
+            g.r2m[id - g.sd.off[2]] = mean_;
+            g.r2q[id - g.sd.off[2]] = var_ + mean_ * mean_;
+        }
+        if (g.mode == DISCOVER_SCORE_MAX) {
+            if (kb == 0) {
+                g.scores[id] = !ok ? nanv : state == 1.0 ? mx : -(mx + ub);
+                cnt += ok;
+            }
+        } else {
+            for (int e = 0; e < 4; e++)
+                if (4 * kb + e < g.T)
+                    g.scores[(int64_t)(4 * kb + e) * g.N + id] = !ok ? nanv : state == 1.0 ? r[e] : -(r[e] + ub);
             if (kb == 0) cnt += ok;
         }
     }
@@ -1869,9 +2101,16 @@ static void launch_pairs(int OPS, ctab<PairArgs> A, const int4* tiles, int64_t n
 }
 
 template <bool FP16>
-static void launch_lp(int cls, const PairArgs& a, const void* ylp, int ldl, hipStream_t st) {
+static void launch_lp(int cls, const PairArgs& a, const void* ylp, int ldl, double delta, hipStream_t st) {
     const unsigned blocks = (unsigned)a.n_tiles;           // one block per (j, 64 i) tile
     if (!blocks) return;
+    if (!FP16) {                                           // BF16: single pass
+        switch (cls) {
+        case 31: k_screen_lp1<31><<<blocks, 256, 0, st>>>(a, ylp, ldl, delta); return;
+        case 28: k_screen_lp1<28><<<blocks, 256, 0, st>>>(a, ylp, ldl, delta); return;
+        default: DSC_FAIL(DISCOVER_E_UNSUPPORTED, "operator class %d", cls);
+        }
+    }
     switch (cls) {
     case 31: k_screen_lp<31, FP16><<<blocks, 256, 0, st>>>(a, ylp, ldl); break;
     case 28: k_screen_lp<28, FP16><<<blocks, 256, 0, st>>>(a, ylp, ldl); break;
@@ -1879,13 +2118,24 @@ static void launch_lp(int cls, const PairArgs& a, const void* ylp, int ldl, hipS
     }
 }
 
-// Guard half-width of the precision forms (see k_screen_lp).
+// Error bound of a low-precision score per unit of sqrt(kappa) (see
+// k_screen_lp and k_screen_lp1): rounding both factors, u = 2^-8 (BF16) or
+// 2^-11 (FP16), FP32 summation over n terms, and for BF16 the FP64 -> FP32
+// step before the rounding (2^-23 for both factors).
 static double lowprec_delta(int precision, int n) {
     const double u = precision == DISCOVER_FP16_GUARD ? std::ldexp(1.0, -11) : std::ldexp(1.0, -8);
     const double g = n * std::ldexp(1.0, -24);
     double d = 2 * u + u * u + 1.01 * g / (1 - g) + 1e-12;
     if (precision == DISCOVER_FP16_GUARD) d += std::ldexp(1.0, -24);
+    else d += std::ldexp(1.0, -23);
     return d;
+}
+
+// Selection margin of a precision form: FP16 stores standardised values
+// (kappa = 1); BF16 stores scores for kappa <= LP1_KAPPA.
+static double lowprec_margin(int precision, int n) {
+    const double d = lowprec_delta(precision, n);
+    return precision == DISCOVER_FP16_GUARD ? d : d * std::sqrt(LP1_KAPPA);
 }
 
 // Description of one search space and its work lists, cached in the
@@ -2354,8 +2604,9 @@ static void screen_all(discover_ctx* ctx, const discover_problem* probs, int nb,
         PairArgs a = pa[b];
         a.tiles = pl.ptiles; a.n_tiles = pl.n_ptiles;
         KTimer kt(ctx, st, "screen_lp");
-        if (fp16) launch_lp<true>(pl.dense_cls, a, P.ylp, P.ldl, st);
-        else launch_lp<false>(pl.dense_cls, a, P.ylp, P.ldl, st);
+        const double dl = lowprec_delta(prm.precision, P.n);
+        if (fp16) launch_lp<true>(pl.dense_cls, a, P.ylp, P.ldl, dl, st);
+        else launch_lp<false>(pl.dense_cls, a, P.ylp, P.ldl, dl, st);
         check_launch("k_screen_lp");
     }
     // 6b. FP64 dense tiles, merged per (operator class, padded targets)
@@ -2658,7 +2909,7 @@ void generate_screen(discover_ctx* ctx, const discover_problem* probs, int nb,
         s.tile_j = P.tile_j;
         margin[b] = 4.0 * P.n * EPS64 * KAPPA_MAX;
         if (prm.precision != DISCOVER_FP64) {
-            s.guard_band = lowprec_delta(prm.precision, P.n);
+            s.guard_band = lowprec_margin(prm.precision, P.n);
             margin[b] = std::max(margin[b], s.guard_band);
         }
         for (int t = 0; t < P.Tl; t++) {
