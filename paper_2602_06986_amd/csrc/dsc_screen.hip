@@ -1260,11 +1260,11 @@ __global__ __launch_bounds__(256) void k_screen_lp(PairArgs g, const void* __res
 // FP32) changes r by at most delta * sqrt(kappa), kappa = sum u^2 / var_n
 // (the same bound as for standardised values, scaled by the size of u
 // relative to its spread).  A candidate with kappa <= LP1_KAPPA stores its
-// score (error within the selection margin 2 delta); up to KAPPA_MAX it
+// score (error within the selection margin 1.1 delta); up to KAPPA_MAX it
 // stores the upper bound -(s + delta sqrt(kappa)) (rescored exactly when it
 // can reach the pool); beyond that it is decided by the FP64 fix-up pass.
 // BF16 keeps FP32's exponent range, so u needs no scaling.
-constexpr double LP1_KAPPA = 4.0;
+constexpr double LP1_KAPPA = 1.21;     // scores stored up to sqrt(kappa) = 1.1 (most shifts are close)
 
 template <int OPS>
 __global__ __launch_bounds__(256) void k_screen_lp1(PairArgs g, const void* __restrict__ Ylp_, int ldl,
