@@ -112,6 +112,7 @@ struct SweepArgs {
     int64_t n_items;
     double* lane_q;           // [n_items][64] (D = 1, 2) or [n_items][256] (D = 3)
     int64_t item0;            // first merged block (D = 3) or merged block of 4 waves (D = 1, 2)
+    const double* theta;      // D = 3: the bound th of the table's shifted Q_ab
 };
 
 __device__ __forceinline__ double fast_rcp(double x) {
@@ -174,12 +175,36 @@ __global__ __launch_bounds__(256) void k_sweep2(ctab<SweepArgs> A, const int* __
 // address: they arrive through scalar loads into SGPRs and enter the FP64
 // FMAs as scalar operands, leaving LDS and the vector memory path to the
 // per-lane G[b][c] stream.
+//
+// Bounded sweep.  Before the sweep, a lower bound theta on the m-th best
+// subset is taken from m subsets in distinct lanes (k_sw3_rows/k_sw3_theta)
+// and lowered by every allowance of the band (th = theta - GRAM_DELTA -
+// 4 SW3_RCP_DELTA - 1e-8).  The table stores Q_ab - th, so the test
+//   e^2 + (Q_ab - th) den > 0   <=>   q > th      (den > 0)
+// costs one FMA and two 32-bit compares per subset; only when some lane of
+// the wave passes it are the wave's exact values (reciprocal, pivot test,
+// minimum) computed.  A lane whose best subset lies above th therefore
+// reports that subset's exact sweep value, as an unbounded sweep would, and
+// every other lane reports a value below th (or -1), which no band
+// threshold can reach: the m lanes that define theta report at least theta,
+// so the threshold is at least theta - GRAM_DELTA - SW3_RCP_DELTA - 1e-12,
+// and a lane is expanded only from that threshold minus another
+// SW3_RCP_DELTA + 1e-9 on.
 constexpr int SW3_A = 4;              // values of a per wave
+constexpr int SW3_MMAX = 16;          // bounded sweep for m up to this
+constexpr double SW3_TH_SLACK = GRAM_DELTA + 4.0 * SW3_RCP_DELTA + 1e-8;
+// high word of PIV_TOL: den > PIV_TOL implies hi(den) >= SW3_HI_PIV
+constexpr int SW3_HI_PIV = (int)(__builtin_bit_cast(unsigned long long, PIV_TOL) >> 32);
 
 struct Sw3Lane {
     double upc, dc, zc;
 };
 
+// Entry of the factor table for (a, b); w = Q_ab - th.  A singular a or
+// pair (a, b), and every (a, b) that cannot start a triple, carries
+// (0, 0, 0, -inf): h_b = 0 leaves den = d_c, and w = -inf makes q = -inf
+// in every form of the sweep (the bounded test fails, the exact value is
+// +inf in negated form, which the minimum skips).
 __device__ __forceinline__ double4 sw3_b_entry(const double* G, int ldg, int S, const double* Ga,
                                                double ica, double ca, int b) {
     const double ub = Ga[b];
@@ -189,7 +214,18 @@ __device__ __forceinline__ double4 sw3_b_entry(const double* G, int ldg, int S, 
         const double hb = 1.0 / db;
         return make_double4(ub, zb * hb, hb, ca * ca * ica + zb * zb * hb);
     }
-    return make_double4(ub, 0.0, 0.0, -1.0);            // singular pair: skipped
+    return make_double4(0.0, 0.0, 0.0, -__builtin_inf());
+}
+
+__device__ __forceinline__ Sw3Lane sw3_lane(const double* G, int ldg, int S, const double* Ga,
+                                            double caa, double ca, int c, bool cok) {
+    Sw3Lane L;
+    const double uc = Ga[c];
+    L.upc = uc * (1.0 / caa);
+    // an out-of-range c gets a negative d_c, so none of its triples passes
+    L.dc = cok ? G[(int64_t)c * ldg + c] - uc * L.upc : -1.0;
+    L.zc = G[(int64_t)c * ldg + S] - ca * L.upc;
+    return L;
 }
 
 __device__ __forceinline__ double sw3_q(const double4& e, const Sw3Lane& L, double Cbc,
@@ -204,21 +240,18 @@ __device__ __forceinline__ double sw3_q(const double4& e, const Sw3Lane& L, doub
 // Table of (a, b) factors, E[b * lde + a], lde >= S + 16.  Row b holds every
 // a < b and the entries a = b .. b + 15 that a block starting below b may
 // also read (a wave's a values reach at most 15 past the block's first a).
-// Entries that cannot form a triple (b <= a, a >= S - 2, a or the pair
-// (a, b) singular) carry h_b = NaN: den is then NaN and fails the pivot
-// test for every c.
 __device__ __forceinline__ void d_sw3_table(const double* __restrict__ G, int ldg, int S,
-                                            double4* __restrict__ E, int lde) {
+                                            double4* __restrict__ E, int lde, double th) {
     const int b = blockIdx.y;
     const int a = blockIdx.x * 256 + threadIdx.x;
     if (a >= lde || a > b + 15) return;
-    double4 e = make_double4(0.0, 0.0, __builtin_nan(""), 0.0);
+    double4 e = make_double4(0.0, 0.0, 0.0, -__builtin_inf());
     if (a < S - 2 && b > a) {
         const double* Ga = G + (int64_t)a * ldg;
         const double caa = Ga[a];
         if (caa > PIV_TOL) {
-            const double4 f = sw3_b_entry(G, ldg, S, Ga, 1.0 / caa, Ga[S], b);
-            if (f.w >= 0.0) e = f;
+            e = sw3_b_entry(G, ldg, S, Ga, 1.0 / caa, Ga[S], b);
+            e.w -= th;
         }
     }
     E[(int64_t)b * lde + a] = e;
@@ -226,11 +259,10 @@ __device__ __forceinline__ void d_sw3_table(const double* __restrict__ G, int ld
 
 // min(low, ok ? x : +huge): the mask selects only the high word (a value
 // with high word 0x7FEFFFFF is a large positive finite number whatever its
-// low word), and the minimum is one v_min_f64.  Both operands are ordinary
-// finite numbers, so the input quieting the compiler adds around fmin (for
-// signalling NaNs) is not needed; the instruction is written out to leave it
-// out.  Its inputs come from plain VALU instructions, never from a
-// transcendental one.
+// low word), and the minimum is one v_min_f64.  In IEEE mode v_min_f64
+// returns the other operand when one is a quiet NaN and never prefers
+// +inf, which the sweep's marked entries rely on; the instruction is written
+// out to leave out the input quieting the compiler adds around fmin.
 __device__ __forceinline__ double sw3_keep(double low, double x, bool ok) {
     const int hi = ok ? __double2hiint(x) : (int)0x7FEFFFFF;
     const double v = __hiloint2double(hi, __double2loint(x));
@@ -241,47 +273,72 @@ __device__ __forceinline__ double sw3_keep(double low, double x, bool ok) {
 
 // The sweep's own value, -q~ with q~ = e^2 * rcp(den) + Q_ab, where rcp is
 // the bare hardware reciprocal (relative error below 2^-24 measured on
-// gfx950; SW3_RCP_DELTA allows 2^-21 of the explained fraction).  The
-// negated form keeps Q_ab a wave-uniform SGPR operand of one VOP3 FMA
-// (a negated addend cannot use the accumulating VOP2 form, which would need
-// Q_ab copied into VGPRs); the lanes track the minimum of -q~.
-__device__ __forceinline__ double sw3_negq(const double4& e, const Sw3Lane& L, double Cbc,
-                                           double& den) {
-    const double Cp = fma(-e.x, L.upc, Cbc);
-    const double ee = fma(-Cp, e.y, L.zc);
-    const double t = Cp * e.z;
-    den = fma(-Cp, t, L.dc);
-    return fma(-(ee * ee), __builtin_amdgcn_rcp(den), -e.w);
+// gfx950; SW3_RCP_DELTA allows 2^-21 of the explained fraction).  w is the
+// table's Q_ab - th; adding th back costs one rounding of Q_ab, far inside
+// the band's allowances.
+__device__ __forceinline__ double sw3_negq(double ee2, double den, double w, double th) {
+    return fma(-ee2, __builtin_amdgcn_rcp(den), -(w + th));
 }
 
-template <bool DIAG>
-__device__ __forceinline__ void sw3_run(const double4* __restrict__ Ew, int lde, const double* colc,
-                                        int ldg, int S, int c, int b, int bend,
-                                        const Sw3Lane (&L)[SW3_A], double (&low)[SW3_A]) {
-    if (b >= bend) return;
-    double Cnext = colc[(int64_t)b * ldg];
-    for (; b < bend; b++) {
-        double Cbc = Cnext;
-        Cnext = colc[(int64_t)min(b + 1, S - 1) * ldg];
-        if (DIAG && b >= c) Cbc = __builtin_nan("");    // lanes with c <= b own no triple here
-        const double4* Eb = Ew + (int64_t)b * lde;
+// One row b of a wave, from its loaded G entry C and factor entries E.  In
+// the bounded form a lane passes when e^2 + w den > 0 (w = Q_ab - th); only
+// when some lane of the wave passes are the exact values of all its lanes
+// formed.  Diagonal lanes with c <= b are cut from the pass mask (lmask)
+// and from the exact update (live); a singular or ill-conditioned triple
+// (den <= PIV_TOL) may pass the test but fails the exact update.
+template <bool BOUND>
+__device__ __forceinline__ void sw3_row(const double4 (&E)[SW3_A], double C, uint64_t lmask, bool live,
+                                        double th, const Sw3Lane (&L)[SW3_A], double (&low)[SW3_A]) {
+    double den[SW3_A], ee2[SW3_A];
+    uint64_t hit = 0;
 #pragma unroll
-        for (int k = 0; k < SW3_A; k++) {
-            const double4 e = Eb[k];
-            double den;
-            const double nq = sw3_negq(e, L[k], Cbc, den);
-            low[k] = sw3_keep(low[k], nq, den > PIV_TOL);
-        }
+    for (int k = 0; k < SW3_A; k++) {
+        const double Cp = fma(-E[k].x, L[k].upc, C);
+        const double ee = fma(-Cp, E[k].y, L[k].zc);
+        const double t = Cp * E[k].z;
+        den[k] = fma(-Cp, t, L[k].dc);
+        ee2[k] = ee * ee;
+        if (BOUND) hit |= __builtin_amdgcn_ballot_w64(__double2hiint(fma(E[k].w, den[k], ee2[k])) > 0);
+    }
+    if (!BOUND || (hit & lmask)) {
+#pragma unroll
+        for (int k = 0; k < SW3_A; k++)
+            low[k] = sw3_keep(low[k], sw3_negq(ee2[k], den[k], E[k].w, th), live && den[k] > PIV_TOL);
     }
 }
 
-__global__ __launch_bounds__(256) void k_sweep3(ctab<SweepArgs> A, const int* __restrict__ bprob) {
+// Rows b .. bend - 1 of a wave.  DIAG: the block's diagonal part, b >= c0,
+// where lanes with c <= b own no triple.  Per row the G entry of the lane's
+// c (a vector load from the row's scalar base) and the wave's four factor
+// entries (scalar loads) are read; eight waves per SIMD cover their latency
+// (issuing the next row's loads ahead needs a second set of 32 SGPRs,
+// which the compiler then spills).
+template <bool DIAG, bool BOUND>
+__device__ __forceinline__ void sw3_run(const double4* __restrict__ Ew, int lde, const double* G,
+                                        int ldg, uint32_t cc, int c0, int b, int bend, double th,
+                                        const Sw3Lane (&L)[SW3_A], double (&low)[SW3_A]) {
+    const int lane = threadIdx.x & 63;
+    const double4* Eb = Ew + (int64_t)b * lde;
+    const double* Gb = G + (int64_t)b * ldg;
+    for (; b < bend; b++, Eb += lde, Gb += ldg) {
+        const double C = Gb[cc];
+        double4 E[SW3_A];
+#pragma unroll
+        for (int k = 0; k < SW3_A; k++) E[k] = Eb[k];
+        // lanes c = c0 + lane > b keep their triples
+        sw3_row<BOUND>(E, C, DIAG ? ~0ull << (b - c0 + 1) : ~0ull, !DIAG || c0 + lane > b, th, L, low);
+    }
+}
+
+// Eight waves per SIMD (64 VGPRs; the few spills sit outside the row loops).
+template <bool BOUND>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_sweep3(ctab<SweepArgs> A, const int* __restrict__ bprob) {
     const SweepArgs& g = tab(A, bprob[blockIdx.x]);
-    DSC_GLOBAL(g.G); DSC_GLOBAL(g.E); DSC_GLOBAL(g.items3); DSC_GLOBAL(g.lane_q);
+    DSC_GLOBAL(g.G); DSC_GLOBAL(g.E); DSC_GLOBAL(g.items3); DSC_GLOBAL(g.lane_q); DSC_GLOBAL(g.theta);
     const int64_t li = (int64_t)blockIdx.x - g.item0;   // block within its problem
     const int4 item = g.items3[li];
     const int a0 = item.x, c0 = item.y;                  // block: a0..a0+15, c0..c0+63, b in [z, w)
-    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wv = wave_id();
     const int lane = threadIdx.x & 63;
     const int c = c0 + lane;
     double* out = g.lane_q + (li * 4 + wv) * (SW3_A * 64);
@@ -289,33 +346,117 @@ __global__ __launch_bounds__(256) void k_sweep3(ctab<SweepArgs> A, const int* __
         for (int k = 0; k < SW3_A; k++) out[k * 64 + lane] = -1.0;
         return;
     }
+    const double th = *g.theta;
     const int aw = a0 + wv * SW3_A;                      // the wave's first a
+    // a lane past the last column evaluates column S - 1 (c > b holds
+    // there) and reports no triple
     const bool cok = c < g.S;
     const int cc = cok ? c : g.S - 1;
-    const double Gcc = g.G[(int64_t)cc * g.ldg + cc], cyc = g.G[(int64_t)cc * g.ldg + g.S];
     Sw3Lane L[SW3_A];
     double low[SW3_A];                                   // min over b of -q~
 #pragma unroll
     for (int k = 0; k < SW3_A; k++) {
         const int ac = min(aw + k, g.S - 1);
         const double* Ga = g.G + (int64_t)ac * g.ldg;
-        const double caa = Ga[ac], ca = Ga[g.S];
-        const double upc = Ga[cc] * (1.0 / caa);
-        L[k].upc = upc;
-        // an out-of-range c makes den NaN, so none of its triples passes
-        L[k].dc = cok ? Gcc - Ga[cc] * upc : __builtin_nan("");
-        L[k].zc = cyc - ca * upc;
+        L[k] = sw3_lane(g.G, g.ldg, g.S, Ga, Ga[ac], Ga[g.S], cc, true);
         low[k] = 1.0;
     }
-    const double* colc = g.G + cc;
     const double4* Ew = g.E + aw;
     const int bstart = max(aw + 1, item.z);
     const int bend = min(min(g.S - 1, c0 + 63), item.w); // b < largest c of the block
-    // b < c0: every lane has c > b; from c0 on, lanes with c <= b are masked
-    sw3_run<false>(Ew, g.lde, colc, g.ldg, g.S, c, bstart, min(bend, c0), L, low);
-    sw3_run<true>(Ew, g.lde, colc, g.ldg, g.S, c, max(bstart, c0), bend, L, low);
+    // b < c0: every lane has c > b; from c0 on, lanes with c <= b are cut
+    sw3_run<false, BOUND>(Ew, g.lde, g.G, g.ldg, (uint32_t)cc, c0, bstart, min(bend, c0), th, L, low);
+    sw3_run<true, BOUND>(Ew, g.lde, g.G, g.ldg, (uint32_t)cc, c0, max(bstart, c0), bend, th, L, low);
 #pragma unroll
-    for (int k = 0; k < SW3_A; k++) out[k * 64 + lane] = -low[k];   // -1: no valid triple
+    for (int k = 0; k < SW3_A; k++) out[k * 64 + lane] = cok ? -low[k] : -1.0;   // -1: no valid triple
+}
+
+// Lower bound for the bounded sweep, step 1: one wave per row a.  b(a) is
+// the partner with the largest Q_ab (ties: smaller b) among b <= S - 2, and
+// rowq[a] the largest sweep value of the triples (a, b(a), c), c > b(a), or
+// -1.  Distinct rows give subsets in distinct sweep lanes (a, c).
+struct ThetaArgs {
+    const double* G;
+    int ldg, S;
+    double* rowq;
+    double* theta;
+};
+
+__device__ __forceinline__ void wave_argmax(double& v, int& i) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        const double ov = __shfl_xor(v, o);
+        const int oi = __shfl_xor(i, o);
+        if (ov > v || (ov == v && oi < i)) { v = ov; i = oi; }
+    }
+}
+
+// grid (row blocks of 4, problems)
+__global__ __launch_bounds__(256) void k_sw3_rows(ctab<ThetaArgs> A) {
+    const ThetaArgs& g = tab(A, blockIdx.y);
+    DSC_GLOBAL(g.G); DSC_GLOBAL(g.rowq);
+    const int a = blockIdx.x * 4 + wave_id();
+    const int lane = threadIdx.x & 63;
+    if (a >= g.S) return;
+    const double* Ga = g.G + (int64_t)a * g.ldg;
+    const double caa = Ga[a], ca = Ga[g.S];
+    double best = -1.0;
+    if (a < g.S - 2 && caa > PIV_TOL) {
+        const double ica = 1.0 / caa;
+        double qb = -1.0;
+        int bb = 0x7fffffff;
+        for (int b = a + 1 + lane; b < g.S - 1; b += 64) {
+            const double4 e = sw3_b_entry(g.G, g.ldg, g.S, Ga, ica, ca, b);
+            if (e.w > qb) { qb = e.w; bb = b; }
+        }
+        wave_argmax(qb, bb);
+        if (qb >= 0.0) {
+            const int b = bb;
+            const double4 e = sw3_b_entry(g.G, g.ldg, g.S, Ga, ica, ca, b);
+            const double* Gb = g.G + (int64_t)b * g.ldg;
+            for (int c = b + 1 + lane; c < g.S; c += 64) {
+                const Sw3Lane L = sw3_lane(g.G, g.ldg, g.S, Ga, caa, ca, c, true);
+                const double Cp = fma(-e.x, L.upc, Gb[c]);
+                const double ee = fma(-Cp, e.y, L.zc);
+                const double den = fma(-Cp, Cp * e.z, L.dc);
+                if (den > PIV_TOL) best = fmax(best, -sw3_negq(ee * ee, den, e.w, 0.0));
+            }
+            int dummy = 0;
+            wave_argmax(best, dummy);
+        }
+    }
+    if (lane == 0) g.rowq[a] = best;
+}
+
+// Step 2, one block per problem: theta = the m-th largest row value (m
+// rounds of a block-wide arg-max, ties to the smaller row), th = theta -
+// SW3_TH_SLACK; with fewer than m rows holding a triple, th = -1 (every
+// subset passes the bounded test).
+__global__ __launch_bounds__(256) void k_sw3_theta(ctab<ThetaArgs> A, int m) {
+    const ThetaArgs& g = tab(A, blockIdx.x);
+    DSC_GLOBAL(g.rowq); DSC_GLOBAL(g.theta);
+    __shared__ double sv[4];
+    __shared__ int si[4];
+    double pv = __builtin_inf();
+    int pi = -1;
+    for (int r = 0; r < m; r++) {
+        double v = -__builtin_inf();
+        int i = 0x7fffffff;
+        for (int a = threadIdx.x; a < g.S; a += 256) {
+            const double x = g.rowq[a];
+            const bool below = x < pv || (x == pv && a > pi);
+            if (below && (x > v || (x == v && a < i))) { v = x; i = a; }
+        }
+        wave_argmax(v, i);
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) { sv[threadIdx.x >> 6] = v; si[threadIdx.x >> 6] = i; }
+        __syncthreads();
+        v = sv[0]; i = si[0];
+        for (int w = 1; w < 4; w++)
+            if (sv[w] > v || (sv[w] == v && si[w] < i)) { v = sv[w]; i = si[w]; }
+        pv = v; pi = i;
+    }
+    if (threadIdx.x == 0) *g.theta = pv >= 0.0 ? pv - SW3_TH_SLACK : -1.0;
 }
 
 // Band expansion.  thr = (m-th best lane value) * (1 - 1e-12) - GRAM_DELTA.
@@ -336,6 +477,7 @@ struct BandArgs {
     int4* pairs;              // D = 3: (a, c, b_lo, b_hi) lanes to expand
     unsigned long long* pcnt;
     int64_t pcap;
+    const double* theta;      // D = 3: the table's shift th
 };
 
 // For D = 3 the lane values carry the sweep's reciprocal error (at most
@@ -380,8 +522,9 @@ __global__ __launch_bounds__(256) void k_band_lanes(ctab<BandArgs> A) {
 // D = 3: one wave per listed (a, c) lane; its lanes split the b range.
 __global__ __launch_bounds__(256) void k_band_expand3(ctab<BandArgs> A) {
     const BandArgs& g = tab(A, blockIdx.y);
-    DSC_GLOBAL(g.G); DSC_GLOBAL(g.E); DSC_GLOBAL(g.sel); DSC_GLOBAL(g.st); DSC_GLOBAL(g.band); DSC_GLOBAL(g.bcnt); DSC_GLOBAL(g.pairs); DSC_GLOBAL(g.pcnt);
+    DSC_GLOBAL(g.G); DSC_GLOBAL(g.E); DSC_GLOBAL(g.sel); DSC_GLOBAL(g.st); DSC_GLOBAL(g.band); DSC_GLOBAL(g.bcnt); DSC_GLOBAL(g.pairs); DSC_GLOBAL(g.pcnt); DSC_GLOBAL(g.theta);
     const double thr = band_thr(g);
+    const double th = *g.theta;
     const int64_t np = min((int64_t)*g.pcnt, g.pcap);
     const int lane = threadIdx.x & 63;
     for (int64_t i = (int64_t)blockIdx.x * 4 + wave_id(); i < np; i += (int64_t)gridDim.x * 4) {
@@ -389,13 +532,10 @@ __global__ __launch_bounds__(256) void k_band_expand3(ctab<BandArgs> A) {
         const int blo = max(a + 1, g.pairs[i].z), bhi = min(c, g.pairs[i].w);
         const double* Ga = g.G + (int64_t)a * g.ldg;
         const double caa = Ga[a], ca = Ga[g.S];
-        Sw3Lane L;                                       // the same arithmetic as the sweep
-        const double uc = Ga[c];
-        L.upc = uc * (1.0 / caa);
-        L.dc = g.G[(int64_t)c * g.ldg + c] - uc * L.upc;
-        L.zc = g.G[(int64_t)c * g.ldg + g.S] - ca * L.upc;
+        const Sw3Lane L = sw3_lane(g.G, g.ldg, g.S, Ga, caa, ca, c, true);   // as in the sweep
         for (int b = blo + lane; b < bhi; b += 64) {
-            const double4 e = g.E[(int64_t)b * g.lde + a];
+            double4 e = g.E[(int64_t)b * g.lde + a];
+            e.w += th;
             double den;
             const double q = sw3_q(e, L, g.G[(int64_t)b * g.ldg + c], den);
             if (den > PIV_TOL && q >= thr) band_push(g, a, b, c);
@@ -561,6 +701,7 @@ struct PrepArgs {
     double *Z, *G, *yy;
     double4* E;               // D = 3 factor table
     int lde;
+    const double* theta;      // D = 3: shift th of the table's Q_ab
 };
 
 // grid (row blocks of 4, problems)
@@ -590,9 +731,9 @@ __global__ __launch_bounds__(256) void k_gram(ctab<PrepArgs> A) {
 // grid (a blocks, b rows, problems)
 __global__ __launch_bounds__(256) void k_sw3_table(ctab<PrepArgs> A) {
     const PrepArgs& a = tab(A, blockIdx.z);
-    DSC_GLOBAL(a.G); DSC_GLOBAL(a.E);
+    DSC_GLOBAL(a.G); DSC_GLOBAL(a.E); DSC_GLOBAL(a.theta);
     if ((int)blockIdx.y >= a.S || (int)blockIdx.x * 256 >= a.lde) return;
-    d_sw3_table(a.G, a.ldg, a.S, a.E, a.lde);
+    d_sw3_table(a.G, a.ldg, a.S, a.E, a.lde, *a.theta);
 }
 
 struct RefitArgs {
@@ -797,17 +938,21 @@ __global__ void k_omp_rmse(const double* __restrict__ rss, int n, double* __rest
 // D = 3 blocks (16 consecutive a, 64 consecutive c).  Column groups of 64
 // are dealt to the 8 XCDs by longest-processing-time on their total work,
 // and block p of the grid runs on XCD p mod 8, so each XCD's L2 holds only
-// its own columns of G; within an XCD the heaviest blocks go first.
-constexpr int SW3_BMAX = 256;         // b iterations per block (bounds the critical path)
+// its own columns of G; within an XCD the heaviest blocks go first, and
+// blocks of equal work that share their a rows and b range run side by side
+// (they read the same factor-table entries).  Chunks of 96 rows give the C(1500, 3)
+// sweep 7112 blocks, about 28 per CU, enough to even out the tail.
+constexpr int SW3_BMAX = 96;          // b iterations per block
 
 static std::vector<int4> sweep3_blocks(int S) {
     const int ngrp = (S + 63) / 64;
     std::vector<std::vector<std::pair<int64_t, int4>>> per_grp(ngrp);
     std::vector<int64_t> gwork(ngrp, 0);
-    for (int g = 0; g < ngrp; g++) {
-        const int c0 = 64 * g, ch = std::min(S, c0 + 64);
+    for (int cg = 0; cg < (S + 63) / 64; cg++) {
+        const int c0 = 64 * cg, ch = std::min(S, c0 + 64);
         for (int a0 = 0; a0 < S - 2 && a0 + 2 < ch; a0 += 16) {
             const int bend = std::min(S - 1, c0 + 63);
+            const int g = cg;
             for (int b0 = a0 + 1; b0 < bend; b0 += SW3_BMAX) {
                 const int b1 = std::min(bend, b0 + SW3_BMAX);
                 const int64_t work = (int64_t)(b1 - b0) * 16;
@@ -830,7 +975,9 @@ static std::vector<int4> sweep3_blocks(int S) {
     for (auto& v : q) {
         std::stable_sort(v.begin(), v.end(), [](const std::pair<int64_t, int4>& x,
                                                 const std::pair<int64_t, int4>& y) {
-            return x.first > y.first;
+            if (x.first != y.first) return x.first > y.first;
+            if (x.second.x != y.second.x) return x.second.x < y.second.x;
+            return x.second.z < y.second.z;
         });
         mx = std::max(mx, v.size());
     }
@@ -920,6 +1067,8 @@ void l0_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D
         v.push_back(ar.add((size_t)(pb.S + 1) * a.ldg * 8));               // G
         v.push_back(ar.add(8));                                            // yy
         v.push_back(ar.add(D == 3 ? (size_t)pb.S * a.lde * 32 : 32));      // E
+        v.push_back(ar.add(8));                                            // th
+        v.push_back(ar.add(D == 3 ? (size_t)pb.S * 8 : 8));                // row values
         Smax = std::max(Smax, pb.S);
         ldemax = std::max(ldemax, a.lde);
         if (D == 3) tot_items3 += ni[b]; else tot_items += ni[b];
@@ -930,8 +1079,10 @@ void l0_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D
         pa[b].G = (double*)(base + o[b][1]);
         pa[b].yy = (double*)(base + o[b][2]);
         pa[b].E = (double4*)(base + o[b][3]);
+        pa[b].theta = (const double*)(base + o[b][4]);
     }
     const ctab<PrepArgs> dpa = ct(ctx->upload("l0_prep", pa, st));
+    const bool bound = D == 3 && m <= SW3_MMAX;
     // 2. Gram matrices (and the D = 3 factor tables)
     {
         KTimer kt(ctx, st, "l0_gram");
@@ -942,6 +1093,19 @@ void l0_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D
     }
     if (D == 3) {
         KTimer kt(ctx, st, "l0_table");
+        if (bound) {                            // the lower bound th of each problem
+            std::vector<ThetaArgs> ta(nb);
+            for (int b = 0; b < nb; b++)
+                ta[b] = ThetaArgs{pa[b].G, pa[b].ldg, probs[b].S, (double*)(base + o[b][5]),
+                                  (double*)(base + o[b][4])};
+            const ctab<ThetaArgs> dta = ct(ctx->upload("l0_theta", ta, st));
+            k_sw3_rows<<<dim3((unsigned)cdiv(Smax, 4), nb), 256, 0, st>>>(dta);
+            k_sw3_theta<<<nb, 256, 0, st>>>(dta, m);
+        } else {                                // unbounded: th = 0
+            std::vector<FillSeg> fz;
+            for (int b = 0; b < nb; b++) fz.push_back(fill_seg(base + o[b][4], 8, 0u));
+            fill_all(ctx, "l0_theta_fill", fz, st);
+        }
         k_sw3_table<<<dim3((unsigned)cdiv(ldemax, 256), (unsigned)Smax, nb), 256, 0, st>>>(dpa);
         check_launch("k_sw3_table");
     }
@@ -970,6 +1134,7 @@ void l0_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D
         g.n_items = ni[b];
         g.lane_q = lane_q + lane0[b];
         g.item0 = blk0[b];
+        g.theta = pa[b].theta;
     }
     const ctab<SweepArgs> dsa = ct(ctx->upload("l0_sweep", sa, st));
     {
@@ -977,7 +1142,8 @@ void l0_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D
         if (tot_blk) {
             if (D == 1) k_sweep1<<<(unsigned)tot_blk, 256, 0, st>>>(dsa, d_bprob);
             else if (D == 2) k_sweep2<<<(unsigned)tot_blk, 256, 0, st>>>(dsa, d_bprob);
-            else k_sweep3<<<(unsigned)tot_blk, 256, 0, st>>>(dsa, d_bprob);
+            else if (bound) k_sweep3<true><<<(unsigned)tot_blk, 256, 0, st>>>(dsa, d_bprob);
+            else k_sweep3<false><<<(unsigned)tot_blk, 256, 0, st>>>(dsa, d_bprob);
         }
         check_launch("k_sweep");
     }
@@ -1026,6 +1192,7 @@ void l0_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D
             g.sel = (uint32_t*)(misc + 32); g.st = (int64_t*)(misc + 16);
             g.band = (int4*)(bb + v[0]); g.bcnt = (unsigned long long*)misc; g.bcap = cap[b];
             g.pairs = (int4*)(bb + v[1]); g.pcnt = (unsigned long long*)misc + 1; g.pcap = cap[b];
+            g.theta = pa[b].theta;
             ra[q] = RadixArgs{g.lane_q, g.n_lanes, m, (uint32_t*)(bb + v[7]), (uint32_t*)(misc + 32),
                               (int64_t*)(misc + 16)};
             fills.push_back(fill_seg(misc, 16, 0u));

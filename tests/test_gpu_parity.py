@@ -238,8 +238,12 @@ def _design(rng, S, n, corr=0.5):
     return F * rng.uniform(0.5, 3.0, size=(S, 1)) + rng.normal(size=(S, 1))
 
 
+# D = 3 with m <= 16 runs the bounded sweep (a lower bound from m rows);
+# m = 17, 20 the unbounded one; S = 4, m = 3 has fewer rows holding a triple
+# than m (the bound is switched off inside the bounded sweep).
 @pytest.mark.parametrize("Dd,S,n,m", [(1, 70, 97, 3), (2, 70, 97, 3), (3, 70, 97, 3), (3, 131, 50, 1),
-                                      (2, 5, 7, 4), (3, 3, 6, 1), (3, 200, 301, 8)])
+                                      (2, 5, 7, 4), (3, 3, 6, 1), (3, 200, 301, 8), (3, 90, 80, 16),
+                                      (3, 90, 80, 17), (3, 70, 97, 20), (3, 4, 9, 3), (3, 5, 9, 10)])
 def test_l0_against_oracle(torch, ctx, D, oracle_mod, Dd, S, n, m):
     O = oracle_mod
     rng = np.random.default_rng(S * 10 + Dd)
@@ -285,6 +289,25 @@ def test_l0_singular_rejected(torch, ctx, D):
     for q in range(20):
         s = set(sub[q].cpu().numpy().tolist())
         assert s != {2, 5}
+
+
+@pytest.mark.parametrize("m", [1, 6, 30])
+def test_l0_d3_singular_and_duplicates(torch, ctx, D, oracle_mod, m):
+    """D = 3 with an exact linear dependency (f5 = f2 + f3, so {2, 3, 5} is
+    singular but fits y perfectly) and an exact duplicate row (f9 = f4):
+    every returned model matches the oracle's, none is singular."""
+    rng = np.random.default_rng(11)
+    F = _design(rng, 40, 60)
+    F[5] = F[2] + F[3]
+    F[9] = F[4]
+    y = F[2] + F[3] - 0.5 * F[5] + 0.4 * F[30] + 0.05 * rng.normal(size=60)
+    ids = np.arange(40, dtype=np.int64) * 7 + 1
+    ref = oracle_mod.l0(F, ids, y, 3, m=m, mode="direct")
+    sub, rmse, coef, _, _ = ctx.l0_fit(dev(torch, F), dev(torch, ids), dev(torch, y), 3, m)
+    for q, mo in enumerate(ref):
+        s = sub[q].cpu().numpy()
+        assert set(s.tolist()) != {2, 3, 5} and not {4, 9} <= set(s.tolist())
+        check_model([int(ids[i]) for i in s], float(rmse[q]), coef[q].cpu().numpy(), mo, y, "q%d" % q)
 
 
 @pytest.mark.parametrize("init", [None, (3, 9)])
