@@ -19,6 +19,9 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-x", "hip",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
+# The Gram kernel's FP64 matrix products keep their accumulators in VGPRs
+# (otherwise they are copied between VGPRs and AGPRs on every chunk).
+EXTRA = {"dsc_l0.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
 
 
 def _obj(src):
@@ -29,7 +32,7 @@ def build(verbose=False):
     os.makedirs(os.path.join(CSRC, "_build"), exist_ok=True)
 
     def one(src):
-        cmd = [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", _obj(src)]
+        cmd = [HIPCC] + FLAGS + EXTRA.get(src, []) + ["-c", os.path.join(CSRC, src), "-o", _obj(src)]
         r = subprocess.run(cmd, capture_output=True, text=True)
         msg = "\n".join(l for l in (r.stdout + r.stderr).splitlines()
                         if "packed-fp32-ops" not in l and l.strip())

@@ -50,50 +50,81 @@ __device__ __forceinline__ void d_l0_prep(int n, int S, const double* __restrict
     if (row == S && lane == 0) *yy = q;
 }
 
-// G = Z Z^T for (S+1) rows: 64x64 tiles (upper triangle only, mirrored),
-// 4x4 outputs per thread, samples staged through LDS in chunks of 16 and
-// read back as double2 pairs.
+// G = Z Z^T for M = S + 1 rows on the FP64 matrix cores.  A block covers a
+// 64 x 64 tile of the upper triangle (mirrored when written), each wave a
+// 32 x 32 quarter as 2 x 2 products of v_mfma_f64_16x16x4f64.  That
+// instruction takes A[i][k] from lane i + 16 k and B[k][j] from lane j + 16 k
+// and leaves D[i][j] in lane j + 16 (i mod 4), register i / 4.  The sum over
+// samples may run in any order, so lane l takes samples k0 + 4 (l / 16) +
+// s at step s of a chunk of 16: its four samples of a row are one 32-byte
+// load, and the four lanes of a row read 128 contiguous bytes.  The next
+// chunk's fragments are loaded while the current chunk's 16 products run.
+// ldz is a multiple of 16 and Z is zero past n, rows are 32-byte aligned.
+typedef double dsc_v4d __attribute__((ext_vector_type(4)));
+
 __device__ __forceinline__ void d_gram(int M, int ldz, int nk, const double* __restrict__ Z,
                                        double* __restrict__ G, int ldg) {
-    __shared__ __align__(16) double As[16][64];
-    __shared__ __align__(16) double Bs[16][64];
     const int bi = blockIdx.y * 64, bj = blockIdx.x * 64;
-    if (bj + 63 < bi) return;                 // lower triangle mirrored below
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    double acc[4][4] = {};
+    if (bj < bi) return;                      // lower triangle mirrored below
+    const int wv = wave_id();
+    const int lane = threadIdx.x & 63;
+    const int wi = bi + 32 * (wv >> 1), wj = bj + 32 * (wv & 1);
+    if (wj + 31 < wi) return;                 // a wave wholly below the diagonal
+    const int r16 = lane & 15, kg = 4 * (lane >> 4);
+    const double* pa[2];
+    const double* pb[2];
+#pragma unroll
+    for (int t = 0; t < 2; t++) {
+        pa[t] = Z + (int64_t)min(wi + 16 * t + r16, M - 1) * ldz + kg;
+        pb[t] = Z + (int64_t)min(wj + 16 * t + r16, M - 1) * ldz + kg;
+    }
+    dsc_v4d acc[2][2];
+#pragma unroll
+    for (int u = 0; u < 2; u++)
+#pragma unroll
+        for (int v = 0; v < 2; v++) acc[u][v] = dsc_v4d{0.0, 0.0, 0.0, 0.0};
+    double4 A[2], B[2];
+#pragma unroll
+    for (int t = 0; t < 2; t++) { A[t] = *(const double4*)pa[t]; B[t] = *(const double4*)pb[t]; }
     for (int k0 = 0; k0 < nk; k0 += 16) {
-        for (int e = threadIdx.x; e < 16 * 64; e += 256) {
-            const int r = e >> 4, kk = e & 15;
-            const int ra = bi + r, rb = bj + r;
-            As[kk][r] = ra < M ? Z[(int64_t)ra * ldz + k0 + kk] : 0.0;
-            Bs[kk][r] = rb < M ? Z[(int64_t)rb * ldz + k0 + kk] : 0.0;
+        double4 An[2], Bn[2];
+        const int kn = min(k0 + 16, nk - 16);     // the last chunk reloads itself
+#pragma unroll
+        for (int t = 0; t < 2; t++) {
+            An[t] = *(const double4*)(pa[t] + kn);
+            Bn[t] = *(const double4*)(pb[t] + kn);
         }
-        __syncthreads();
 #pragma unroll
-        for (int kk = 0; kk < 16; kk++) {
-            const double2 a01 = *(const double2*)&As[kk][ty * 4];
-            const double2 a23 = *(const double2*)&As[kk][ty * 4 + 2];
-            const double2 b01 = *(const double2*)&Bs[kk][tx * 4];
-            const double2 b23 = *(const double2*)&Bs[kk][tx * 4 + 2];
-            const double a[4] = {a01.x, a01.y, a23.x, a23.y};
-            const double b[4] = {b01.x, b01.y, b23.x, b23.y};
+        for (int u = 0; u < 2; u++)
 #pragma unroll
-            for (int u = 0; u < 4; u++)
+            for (int v = 0; v < 2; v++) {
+                acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[u].x, B[v].x, acc[u][v], 0, 0, 0);
+                acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[u].y, B[v].y, acc[u][v], 0, 0, 0);
+                acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[u].z, B[v].z, acc[u][v], 0, 0, 0);
+                acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[u].w, B[v].w, acc[u][v], 0, 0, 0);
+            }
+        // the loaded fragments pass through an empty asm: without it the
+        // compiler folds this load into a load at the top of the next chunk
+        // that waits for its own result
 #pragma unroll
-                for (int v = 0; v < 4; v++) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+        for (int t = 0; t < 2; t++) {
+            asm("" : "+v"(An[t].x), "+v"(An[t].y), "+v"(An[t].z), "+v"(An[t].w));
+            asm("" : "+v"(Bn[t].x), "+v"(Bn[t].y), "+v"(Bn[t].z), "+v"(Bn[t].w));
+            A[t] = An[t]; B[t] = Bn[t];
         }
-        __syncthreads();
     }
 #pragma unroll
-    for (int u = 0; u < 4; u++)
+    for (int u = 0; u < 2; u++)
 #pragma unroll
-        for (int v = 0; v < 4; v++) {
-            const int i = bi + ty * 4 + u, j = bj + tx * 4 + v;
-            if (i < M && j < M && i <= j) {
-                G[(int64_t)i * ldg + j] = acc[u][v];
-                G[(int64_t)j * ldg + i] = acc[u][v];
+        for (int v = 0; v < 2; v++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int i = wi + 16 * u + (lane >> 4) + 4 * r, j = wj + 16 * v + r16;
+                if (i < M && j < M && i <= j) {
+                    G[(int64_t)i * ldg + j] = acc[u][v][r];
+                    G[(int64_t)j * ldg + i] = acc[u][v][r];
+                }
             }
-        }
 }
 
 // ----------------------------------------------------------------- sweep
