@@ -223,8 +223,11 @@ discover_status discover_l0_fit(discover_ctx* ctx, const discover_l0_problem* pr
  * smaller candidate ID) and refit y on [1, active rows] by Householder QR,
  * until D_max rows are active.
  *
- *   init_active  device int32 [n_problems][n_init] warm start (rows), or NULL (n_init = 0)
- *   out_active   device int32 [n_problems][D_max] rows in order of addition
+ *   init_active  device int32 [n_problems][n_init] warm start (rows), or NULL (n_init = 0);
+ *                a row outside 0..S-1 or already listed is dropped, and the model then
+ *                ends with fewer than D_max rows
+ *   out_active   device int32 [n_problems][D_max] rows in order of addition (-1 past the
+ *                model's rows)
  *   out_coef     device double [n_problems][D_max+1], intercept first, then the rows
  *                in order of addition
  *   out_rmse     device double [n_problems]
@@ -258,6 +261,11 @@ discover_status discover_omp(discover_ctx* ctx, const discover_l0_problem* probs
  *   out_subsets  device int32 [n_problems][D][m][3] rows of the subspace (first d used, rest -1)
  *   out_rmse     device double [n_problems][D][m]
  *   out_coef     device double [n_problems][D][m][4] intercept first (first d+1 used, rest NaN)
+ *   omp_D        0, or D < omp_D <= DISCOVER_MAX_D: the best D-model of each dataset is then
+ *                extended by OMP (as discover_omp, warm start = its rows) over the subspace
+ *   out_omp_active  device int32 [n_problems][omp_D] subspace rows (NULL when omp_D = 0)
+ *   out_omp_coef    device double [n_problems][omp_D+1] intercept first (NULL when omp_D = 0)
+ *   out_omp_rmse    device double [n_problems] (NULL when omp_D = 0)
  *   out_replayed host int32, or NULL: 1 when a captured graph was replayed, 0 when
  *                the call ran eagerly, -1 when it ran eagerly and capturing the graph
  *                for later calls failed (discover_last_error says why)
@@ -266,8 +274,9 @@ discover_status discover_sisso_batch(discover_ctx* ctx, const discover_problem* 
                                      int32_t n_problems, const discover_screen_params* prm,
                                      int32_t D, int32_t m, int32_t use_graph,
                                      int64_t* out_ids, double* out_scores, int32_t* out_subsets,
-                                     double* out_rmse, double* out_coef, int32_t* out_replayed,
-                                     void* stream);
+                                     double* out_rmse, double* out_coef, int32_t omp_D,
+                                     int32_t* out_omp_active, double* out_omp_coef,
+                                     double* out_omp_rmse, int32_t* out_replayed, void* stream);
 
 /* Number of raw candidates |P_R| of a search space (host only). */
 int64_t discover_count(int32_t p, const discover_screen_params* prm);
@@ -282,6 +291,13 @@ discover_status discover_decode(int32_t p, const discover_screen_params* prm, in
  * number of launches and the summed event time (ms) since the last reset
  * for one kernel name ("screen_pairs", "l0_sweep", ...). */
 discover_status discover_set_timing(discover_ctx* ctx, int32_t enable);
+/* Kernel names (comma-separated, e.g. "l0_sweep3"; NULL or "" for none)
+ * whose launches are also bracketed by events inside graphs captured by
+ * discover_sisso_batch, so that replays report their time while timing is
+ * on.  Graphs captured before the change are discarded (recaptured on the
+ * next call).  Event-record nodes cost some microseconds each: name only
+ * the kernels to be measured. */
+discover_status discover_set_graph_timing(discover_ctx* ctx, const char* names);
 discover_status discover_timing(discover_ctx* ctx, const char* kernel, int64_t* launches,
                                 double* total_ms);
 discover_status discover_reset_timing(discover_ctx* ctx);

@@ -67,7 +67,7 @@ class L0Stats(C.Structure):
 SYMBOLS = ("discover_create", "discover_destroy", "discover_last_error",
            "discover_generate_screen", "discover_l0_fit", "discover_omp", "discover_count",
            "discover_decode", "discover_set_timing", "discover_timing", "discover_reset_timing",
-           "discover_sisso_batch")
+           "discover_sisso_batch", "discover_set_graph_timing")
 
 _lib = None
 
@@ -100,7 +100,8 @@ def lib():
         L.discover_reset_timing.argtypes = [P]
         L.discover_sisso_batch.argtypes = [P, C.POINTER(Problem), C.c_int32, C.POINTER(ScreenParams),
                                            C.c_int32, C.c_int32, C.c_int32, P, P, P, P, P,
-                                           C.POINTER(C.c_int32), P]
+                                           C.c_int32, P, P, P, C.POINTER(C.c_int32), P]
+        L.discover_set_graph_timing.argtypes = [P, C.c_char_p]
         _lib = L
     return _lib
 
@@ -172,6 +173,10 @@ class Context:
     # ------------------------------------------------------------ timing
     def set_timing(self, on=True):
         _check(lib().discover_set_timing(self.h, 1 if on else 0))
+
+    def set_graph_timing(self, names=()):
+        """Kernel timer names also timed inside captured graphs (replays)."""
+        _check(lib().discover_set_graph_timing(self.h, ",".join(names).encode()))
 
     def reset_timing(self):
         _check(lib().discover_reset_timing(self.h))
@@ -377,27 +382,33 @@ class Context:
             targets = [fits[b][3] for b in range(nb)]
         return [{"dims": dims[b], "S_ids": S_ids[b], "F": F[b]} for b in range(nb)]
 
-    def sisso_batch_graph(self, Xs, ys, prm, D, m=1, units=None, use_graph=True):
+    def sisso_batch_graph(self, Xs, ys, prm, D, m=1, units=None, use_graph=True, omp_D=0):
         """The batched SISSO loop as one library call (discover_sisso_batch):
         the first call with given inputs runs eagerly and captures a
         hipGraph, later calls with the same input tensors replay it.  The
         output tensors are kept per input set and reused (and overwritten)
         by later calls.  Returns (ids [nb][D][k], scores [nb][D][k],
         subsets [nb][D][m][3], rmse [nb][D][m], coef [nb][D][m][4], replayed) with
-        replayed 1 (graph replayed), 0 (eager) or -1 (eager; capture failed)."""
+        replayed 1 (graph replayed), 0 (eager) or -1 (eager; capture failed).
+        With omp_D > D the best D-model of each dataset is extended by OMP
+        and the result gains a seventh entry, (active [nb][omp_D] subspace
+        rows, coef [nb][omp_D + 1], rmse [nb])."""
         torch = self.torch
         import numpy as np
         nb = len(Xs)
         dev = Xs[0].device
-        key = (tuple(x.data_ptr() for x in Xs), tuple(y.data_ptr() for y in ys), D, m, prm.k)
+        key = (tuple(x.data_ptr() for x in Xs), tuple(y.data_ptr() for y in ys), D, m, prm.k, omp_D)
         cache = self.__dict__.setdefault("_sisso_out", {})
         if key not in cache:
             cache[key] = (torch.empty((nb, D, prm.k), dtype=torch.int64, device=dev),
                           torch.empty((nb, D, prm.k), dtype=torch.float64, device=dev),
                           torch.empty((nb, D, m, 3), dtype=torch.int32, device=dev),
                           torch.empty((nb, D, m), dtype=torch.float64, device=dev),
-                          torch.empty((nb, D, m, 4), dtype=torch.float64, device=dev))
-        ids, sc, sub, rmse, coef = cache[key]
+                          torch.empty((nb, D, m, 4), dtype=torch.float64, device=dev),
+                          torch.empty((nb, max(omp_D, 1)), dtype=torch.int32, device=dev),
+                          torch.empty((nb, max(omp_D, 1) + 1), dtype=torch.float64, device=dev),
+                          torch.empty((nb,), dtype=torch.float64, device=dev))
+        ids, sc, sub, rmse, coef, oact, ocoef, ormse = cache[key]
         pbs = (Problem * nb)()
         keep = []
         for b in range(nb):
@@ -413,12 +424,15 @@ class Context:
             pbs[b].X, pbs[b].ldx = x.data_ptr(), n_
             pbs[b].Y, pbs[b].ldy = y.data_ptr(), n_
         rep = C.c_int32(0)
+        po = (oact.data_ptr(), ocoef.data_ptr(), ormse.data_ptr()) if omp_D else (None, None, None)
         _check(lib().discover_sisso_batch(self.h, pbs, nb, C.byref(prm), D, m, 1 if use_graph else 0,
                                           ids.data_ptr(), sc.data_ptr(), sub.data_ptr(),
-                                          rmse.data_ptr(), coef.data_ptr(), C.byref(rep),
-                                          _stream_handle(torch, dev)))
+                                          rmse.data_ptr(), coef.data_ptr(), omp_D, po[0], po[1], po[2],
+                                          C.byref(rep), _stream_handle(torch, dev)))
         if rep.value < 0:
             self.capture_error = lib().discover_last_error().decode()
+        if omp_D:
+            return ids, sc, sub, rmse, coef, int(rep.value), (oact, ocoef, ormse)
         return ids, sc, sub, rmse, coef, int(rep.value)
 
     def sisso(self, X, y, prm, D, units=None, n_resid=1, omp_D=0):

@@ -109,6 +109,24 @@ extern "C" discover_status discover_set_timing(discover_ctx* ctx, int32_t enable
     });
 }
 
+extern "C" discover_status discover_set_graph_timing(discover_ctx* ctx, const char* names) {
+    using namespace dsc;
+    return guarded([&] {
+        DSC_REQUIRE(ctx, "ctx is NULL");
+        std::set<std::string> want;
+        for (const char* p = names; p && *p;) {
+            const char* e = std::strchr(p, ',');
+            const size_t len = e ? (size_t)(e - p) : std::strlen(p);
+            if (len) want.insert(std::string(p, len));
+            p = e ? e + 1 : p + len;
+        }
+        if (want != ctx->graph_timed) {
+            ctx->graph_timed.swap(want);
+            ctx->generation++;                  // graphs captured before are not replayed
+        }
+    });
+}
+
 extern "C" discover_status discover_timing(discover_ctx* ctx, const char* kernel, int64_t* launches,
                                            double* total_ms) {
     using namespace dsc;

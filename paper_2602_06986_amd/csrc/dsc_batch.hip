@@ -38,9 +38,18 @@ struct SissoGraph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     uint64_t generation = 0;
+    std::vector<discover_ctx::Pending> timers;   // event pairs recorded inside the graph
+    void drop_timers() {
+        for (auto& t : timers) {
+            if (hipEventDestroy(t.a) != hipSuccess) { /* ignore */ }
+            if (hipEventDestroy(t.b) != hipSuccess) { /* ignore */ }
+        }
+        timers.clear();
+    }
     ~SissoGraph() {
         if (exec && hipGraphExecDestroy(exec) != hipSuccess) { /* ignore */ }
         if (graph && hipGraphDestroy(graph) != hipSuccess) { /* ignore */ }
+        drop_timers();
     }
 };
 
@@ -54,6 +63,10 @@ struct SissoCall {
     int32_t* sub;
     double* rmse;
     double* coef;
+    int omp_D;
+    int32_t* omp_active;
+    double* omp_coef;
+    double* omp_rmse;
 };
 
 // The whole loop on stream st; while capturing, the checks of every
@@ -108,6 +121,21 @@ static void sisso_sequence(discover_ctx* ctx, const SissoCall& c, const std::str
         }
         l0_batch(ctx, lp.data(), nb, d, m, lo, l0st, st, ctx->capturing ? &bc : nullptr);
     }
+    if (c.omp_D > D) {
+        // the best D-model of each dataset, extended by OMP over its subspace
+        ctx->tag = gtag + "omp";
+        std::vector<discover_l0_problem> op(nb);
+        for (int b = 0; b < nb; b++) {
+            op[b].n = c.probs[b].n;
+            op[b].S = D * k;
+            op[b].F = F + (size_t)b * D * k * ldf;
+            op[b].ldf = (int64_t)ldf;
+            op[b].ids = c.ids + (int64_t)b * D * k;
+            op[b].y = c.probs[b].Y;
+        }
+        omp_batch(ctx, op.data(), nb, c.omp_D, c.sub + (int64_t)(D - 1) * m * 3, D, (int64_t)D * m * 3,
+                  c.omp_active, c.omp_coef, c.omp_rmse, nullptr, 0, st);
+    }
     ctx->tag = gtag;
     if (!ctx->capturing) {
         // one selection list and one band per dataset and dimension: size the
@@ -127,8 +155,10 @@ static void sisso_sequence(discover_ctx* ctx, const SissoCall& c, const std::str
 
 static std::string sisso_key(const SissoCall& c) {
     std::string key((const char*)&c.prm, sizeof c.prm);
-    const int64_t f[9] = {c.nb, c.D, c.m, c.k, (int64_t)(intptr_t)c.ids, (int64_t)(intptr_t)c.sc,
-                          (int64_t)(intptr_t)c.sub, (int64_t)(intptr_t)c.rmse, (int64_t)(intptr_t)c.coef};
+    const int64_t f[13] = {c.nb, c.D, c.m, c.k, (int64_t)(intptr_t)c.ids, (int64_t)(intptr_t)c.sc,
+                           (int64_t)(intptr_t)c.sub, (int64_t)(intptr_t)c.rmse, (int64_t)(intptr_t)c.coef,
+                           c.omp_D, (int64_t)(intptr_t)c.omp_active, (int64_t)(intptr_t)c.omp_coef,
+                           (int64_t)(intptr_t)c.omp_rmse};
     key.append((const char*)f, sizeof f);
     for (int b = 0; b < c.nb; b++) {
         const discover_problem& p = c.probs[b];
@@ -146,6 +176,8 @@ extern "C" discover_status discover_sisso_batch(discover_ctx* ctx, const discove
                                                 int32_t D, int32_t m, int32_t use_graph,
                                                 int64_t* out_ids, double* out_scores,
                                                 int32_t* out_subsets, double* out_rmse, double* out_coef,
+                                                int32_t omp_D, int32_t* out_omp_active,
+                                                double* out_omp_coef, double* out_omp_rmse,
                                                 int32_t* out_replayed, void* stream) {
     using namespace dsc;
     return guarded([&] {
@@ -153,6 +185,11 @@ extern "C" discover_status discover_sisso_batch(discover_ctx* ctx, const discove
         DSC_REQUIRE(D >= 1 && D <= 3, "D = %d outside 1..3", D);
         DSC_REQUIRE(m >= 1 && m <= DISCOVER_MAX_TARGETS, "m = %d outside 1..%d", m, DISCOVER_MAX_TARGETS);
         DSC_REQUIRE(out_ids && out_scores && out_subsets && out_rmse && out_coef, "outputs required");
+        DSC_REQUIRE(omp_D == 0 || (omp_D > D && omp_D <= DISCOVER_MAX_D), "omp_D = %d: 0 or %d..%d",
+                    omp_D, D + 1, DISCOVER_MAX_D);
+        DSC_REQUIRE(omp_D == 0 || (out_omp_active && out_omp_coef && out_omp_rmse),
+                    "OMP outputs required");
+        DSC_REQUIRE(omp_D == 0 || (int64_t)D * prm->k >= omp_D, "omp_D exceeds the subspace");
         DSC_REQUIRE(prm->rung >= 0 && prm->rung <= DISCOVER_MAX_RUNG && prm->k >= 1, "rung/k");
         DSC_REQUIRE(prm->score_mode == DISCOVER_SCORE_PER_TARGET, "the first dimension screens one target");
         int nmax = 0;
@@ -170,7 +207,8 @@ extern "C" discover_status discover_sisso_batch(discover_ctx* ctx, const discove
         hipStream_t caller = (hipStream_t)stream;
         if (out_replayed) *out_replayed = 0;
         SissoCall c{probs, n_problems, *prm, D, m, prm->k, (int)cdiv(nmax, 64) * 64,
-                    out_ids, out_scores, out_subsets, out_rmse, out_coef};
+                    out_ids, out_scores, out_subsets, out_rmse, out_coef, omp_D, out_omp_active,
+                    out_omp_coef, out_omp_rmse};
         // all work runs on the context's own stream (a capture needs a
         // non-default stream); the call returns with its results ready
         hipStream_t gs = nullptr;
@@ -200,6 +238,15 @@ extern "C" discover_status discover_sisso_batch(discover_ctx* ctx, const discove
             int h = 1;
             DSC_HIP(hipMemcpyAsync(&h, verdict, 4, hipMemcpyDeviceToHost, gs));
             DSC_HIP(hipStreamSynchronize(gs));
+            if (ctx->timing)
+                for (auto& t : G->timers) {
+                    float ms = 0.f;
+                    if (hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
+                        auto& acc = ctx->times[t.name];
+                        acc.first += 1;
+                        acc.second += ms;
+                    }
+                }
             if (h == 0) {
                 if (out_replayed) *out_replayed = 1;
                 return;
@@ -224,15 +271,20 @@ extern "C" discover_status discover_sisso_batch(discover_ctx* ctx, const discove
         // capture the same sequence for later calls
         if (G->exec) { if (hipGraphExecDestroy(G->exec) != hipSuccess) { } G->exec = nullptr; }
         if (G->graph) { if (hipGraphDestroy(G->graph) != hipSuccess) { } G->graph = nullptr; }
+        G->drop_timers();
         const uint64_t gen0 = ctx->generation;
         ctx->capturing = true;
+        ctx->graph_pending.clear();
         DSC_HIP(hipStreamBeginCapture(gs, hipStreamCaptureModeRelaxed));
         discover_status cap_status = guarded([&] { sisso_sequence(ctx, c, gtag, gs); });
         hipGraph_t graph = nullptr;
         const hipError_t ec = hipStreamEndCapture(gs, &graph);
         ctx->capturing = false;
         ctx->tag.clear();
+        G->timers.swap(ctx->graph_pending);
+        ctx->graph_pending.clear();
         if (cap_status != DISCOVER_OK || ec != hipSuccess || !graph || ctx->generation != gen0) {
+            G->drop_timers();
             if (graph && hipGraphDestroy(graph) != hipSuccess) { }
             if (cap_status == DISCOVER_OK) {
                 if (ec != hipSuccess) set_error("graph capture failed: %s", hipGetErrorString(ec));

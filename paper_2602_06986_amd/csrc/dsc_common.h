@@ -11,6 +11,7 @@
 #include <cstring>
 #include <algorithm>
 #include <map>
+#include <set>
 #include <memory>
 #include <string>
 #include <utility>
@@ -84,6 +85,11 @@ struct discover_ctx {
     };
     std::vector<Pending> pending;
     std::vector<hipEvent_t> free_events;
+    // Timer names whose kernels are bracketed by events inside captured
+    // graphs too (each replay then reports their time), and the event pairs
+    // recorded by the capture in progress.
+    std::set<std::string> graph_timed;
+    std::vector<Pending> graph_pending;
     std::map<std::string, std::shared_ptr<void>> plans;   // cached search-space plans
     std::map<std::string, std::shared_ptr<void>> batches; // cached batch plans / graphs
     std::map<std::string, std::vector<char>> shadows;     // host copies of uploaded arguments
@@ -193,21 +199,55 @@ struct discover_ctx {
 
 namespace dsc {
 
+// Records ev as a node of the graph being captured on s (a plain
+// hipEventRecord during a capture does not become a graph node).
+inline hipError_t capture_event_record(hipStream_t s, hipEvent_t ev) {
+    hipStreamCaptureStatus cs;
+    unsigned long long id = 0;
+    hipGraph_t g = nullptr;
+    const hipGraphNode_t* deps = nullptr;
+    size_t nd = 0;
+    hipError_t e = hipStreamGetCaptureInfo_v2(s, &cs, &id, &g, &deps, &nd);
+    if (e != hipSuccess) return e;
+    if (cs != hipStreamCaptureStatusActive || !g) return hipErrorStreamCaptureInvalidated;
+    hipGraphNode_t node;
+    e = hipGraphAddEventRecordNode(&node, g, deps, nd, ev);
+    if (e != hipSuccess) return e;
+    return hipStreamUpdateCaptureDependencies(s, &node, 1, hipStreamSetCaptureDependencies);
+}
+
 // Brackets one kernel launch with HIP events on its stream when timing is on.
 struct KTimer {
     discover_ctx* c;
     hipStream_t s;
     const char* name;
     hipEvent_t a = nullptr, b = nullptr;
+    bool graph = false;
     KTimer(discover_ctx* c_, hipStream_t s_, const char* n) : c(c_), s(s_), name(n) {
         if (c->timing && !c->capturing) {
             a = c->event();
             b = c->event();
             DSC_HIP(hipEventRecord(a, s));
+        } else if (c->capturing && c->graph_timed.count(name)) {
+            // event-record nodes of the graph: the pair belongs to the graph
+            graph = true;
+            DSC_HIP(hipEventCreate(&a));
+            if (hipEventCreate(&b) != hipSuccess) {
+                if (hipEventDestroy(a) != hipSuccess) { /* ignore */ }
+                a = nullptr;
+                DSC_FAIL(DISCOVER_E_HIP, "event creation failed");
+            }
+            c->graph_pending.push_back({name, a, b});
+            DSC_HIP(capture_event_record(s, a));
         }
     }
     ~KTimer() {
-        if (a && hipEventRecord(b, s) == hipSuccess) c->pending.push_back({name, a, b});
+        if (!a) return;
+        if (graph) {
+            if (capture_event_record(s, b) != hipSuccess) { /* the capture reports it */ }
+        } else if (hipEventRecord(b, s) == hipSuccess) {
+            c->pending.push_back({name, a, b});
+        }
     }
 };
 

@@ -58,4 +58,11 @@ void l0_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D
               const std::vector<L0Out>& outs, std::vector<discover_l0_stats>& stats,
               hipStream_t st, std::vector<BandCheck>* checks = nullptr);
 
+// Orthogonal matching pursuit of every problem of a call (validated
+// arguments); problem b starts from the n_init rows init_active + b *
+// init_ld.  Outside capture the call synchronises.
+void omp_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D_max,
+               const int32_t* init_active, int n_init, int64_t init_ld, int32_t* out_active,
+               double* out_coef, double* out_rmse, double* out_resid, int64_t ldr, hipStream_t st);
+
 }  // namespace dsc

@@ -955,10 +955,20 @@ __global__ __launch_bounds__(256) void k_row_norm(int S, int ldz, const double* 
 }
 
 // OMP set-up and result, as kernels so that no host copy is needed.
+// Warm start: the rows of init that lie in 0..S-1, first occurrences only,
+// in order; a missing or repeated row leaves the model one row shorter.
 __global__ void k_omp_init(int32_t* __restrict__ active, int D_max, const int32_t* __restrict__ init,
-                           int n_init, int32_t* __restrict__ nact) {
-    for (int q = threadIdx.x; q < D_max; q += blockDim.x) active[q] = q < n_init ? init[q] : -1;
-    if (threadIdx.x == 0) *nact = n_init;
+                           int n_init, int S, int32_t* __restrict__ nact) {
+    if (threadIdx.x != 0) return;
+    int c = 0;
+    for (int q = 0; q < n_init; q++) {
+        const int r = init[q];
+        bool keep = r >= 0 && r < S;
+        for (int t = 0; t < c; t++) keep = keep && active[t] != r;
+        if (keep) active[c++] = r;
+    }
+    for (int q = c; q < D_max; q++) active[q] = -1;
+    *nact = c;
 }
 
 __global__ void k_omp_rmse(const double* __restrict__ rss, int n, double* __restrict__ out) {
@@ -1347,6 +1357,49 @@ extern "C" discover_status discover_l0_fit(discover_ctx* ctx, const discover_l0_
     });
 }
 
+namespace dsc {
+
+void omp_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D_max,
+               const int32_t* init_active, int n_init, int64_t init_ld, int32_t* out_active,
+               double* out_coef, double* out_rmse, double* out_resid, int64_t ldr, hipStream_t st) {
+    for (int b = 0; b < nb; b++) {
+        const discover_l0_problem& pb = probs[b];
+        const std::string sfx = std::to_string(b);
+        const int ldz = (int)cdiv(pb.n, 16) * 16;
+        double* Z = ctx->buf<double>("ompZ" + sfx, (size_t)(pb.S + 1) * ldz);
+        double* yy = ctx->buf<double>("ompyy" + sfx, 1);
+        int32_t* active = out_active + (int64_t)b * D_max;
+        int32_t* nact = ctx->buf<int32_t>("ompn" + sfx, 1);
+        double* g = ctx->buf<double>("ompg" + sfx, pb.S);
+        double* nrm = ctx->buf<double>("ompnrm" + sfx, pb.S);
+        double* r = out_resid ? out_resid + (int64_t)b * ldr : ctx->buf<double>("ompr" + sfx, pb.n);
+        double* A = ctx->buf<double>("ompA" + sfx, (size_t)(D_max + 2) * pb.n);
+        double* rss = ctx->buf<double>("omprss" + sfx, 1);
+        double* coef = out_coef + (int64_t)b * (D_max + 1);
+        KTimer kt(ctx, st, "omp");
+        k_l0_prep_one<<<(unsigned)cdiv(pb.S + 1, 4), 256, 0, st>>>(pb.n, pb.S, pb.F, pb.ldf, pb.y,
+                                                                   ldz, Z, yy);
+        k_row_norm<<<(unsigned)cdiv(pb.S, 4), 256, 0, st>>>(pb.S, ldz, Z, pb.n, nrm);
+        k_omp_init<<<1, 64, 0, st>>>(active, D_max, n_init ? init_active + (int64_t)b * init_ld : nullptr,
+                                     n_init, pb.S, nact);
+        k_omp_fit<<<1, 256, 0, st>>>(pb.n, pb.F, pb.ldf, pb.y, active, nact, A, coef, rss, r);
+        for (int step = n_init; step < D_max; step++) {
+            k_omp_corr<<<(unsigned)cdiv(pb.S, 4), 256, 0, st>>>(pb.n, pb.S, Z, ldz, r, active,
+                                                                nact, g);
+            k_omp_pick<<<1, 256, 0, st>>>(pb.S, g, pb.ids, nrm, active, nact);
+            k_omp_fit<<<1, 256, 0, st>>>(pb.n, pb.F, pb.ldf, pb.y, active, nact, A, coef, rss, r);
+        }
+        k_omp_rmse<<<1, 64, 0, st>>>(rss, pb.n, out_rmse + b);
+        check_launch("omp");
+    }
+    if (!ctx->capturing) {
+        DSC_HIP(hipStreamSynchronize(st));
+        ctx->resolve_timing();
+    }
+}
+
+}  // namespace dsc
+
 extern "C" discover_status discover_omp(discover_ctx* ctx, const discover_l0_problem* probs,
                                         int32_t n_problems, int32_t D_max, const int32_t* init_active,
                                         int32_t n_init, int32_t* out_active, double* out_coef,
@@ -1367,40 +1420,7 @@ extern "C" discover_status discover_omp(discover_ctx* ctx, const discover_l0_pro
             DSC_REQUIRE(!out_resid || ldr >= p.n, "problem %d: ldr < n", b);
         }
         DSC_HIP(hipSetDevice(ctx->device));
-        hipStream_t st = (hipStream_t)stream;
-        for (int b = 0; b < n_problems; b++) {
-            const discover_l0_problem& pb = probs[b];
-            const std::string sfx = std::to_string(b);
-            const int ldz = (int)cdiv(pb.n, 16) * 16;
-            double* Z = ctx->buf<double>("ompZ" + sfx, (size_t)(pb.S + 1) * ldz);
-            double* yy = ctx->buf<double>("ompyy" + sfx, 1);
-            int32_t* active = out_active + (int64_t)b * D_max;
-            int32_t* nact = ctx->buf<int32_t>("ompn" + sfx, 1);
-            double* g = ctx->buf<double>("ompg" + sfx, pb.S);
-            double* nrm = ctx->buf<double>("ompnrm" + sfx, pb.S);
-            double* r = out_resid ? out_resid + (int64_t)b * ldr : ctx->buf<double>("ompr" + sfx, pb.n);
-            double* A = ctx->buf<double>("ompA" + sfx, (size_t)(D_max + 2) * pb.n);
-            double* rss = ctx->buf<double>("omprss" + sfx, 1);
-            double* coef = out_coef + (int64_t)b * (D_max + 1);
-            KTimer kt(ctx, st, "omp");
-            k_l0_prep_one<<<(unsigned)cdiv(pb.S + 1, 4), 256, 0, st>>>(pb.n, pb.S, pb.F, pb.ldf, pb.y,
-                                                                       ldz, Z, yy);
-            k_row_norm<<<(unsigned)cdiv(pb.S, 4), 256, 0, st>>>(pb.S, ldz, Z, pb.n, nrm);
-            k_omp_init<<<1, 64, 0, st>>>(active, D_max, n_init ? init_active + (int64_t)b * n_init : nullptr,
-                                         n_init, nact);
-            k_omp_fit<<<1, 256, 0, st>>>(pb.n, pb.F, pb.ldf, pb.y, active, nact, A, coef, rss, r);
-            for (int step = n_init; step < D_max; step++) {
-                k_omp_corr<<<(unsigned)cdiv(pb.S, 4), 256, 0, st>>>(pb.n, pb.S, Z, ldz, r, active,
-                                                                    nact, g);
-                k_omp_pick<<<1, 256, 0, st>>>(pb.S, g, pb.ids, nrm, active, nact);
-                k_omp_fit<<<1, 256, 0, st>>>(pb.n, pb.F, pb.ldf, pb.y, active, nact, A, coef, rss, r);
-            }
-            k_omp_rmse<<<1, 64, 0, st>>>(rss, pb.n, out_rmse + b);
-            check_launch("omp");
-        }
-        if (!ctx->capturing) {
-            DSC_HIP(hipStreamSynchronize(st));
-            ctx->resolve_timing();
-        }
+        omp_batch(ctx, probs, n_problems, D_max, init_active, n_init, n_init, out_active, out_coef,
+                  out_rmse, out_resid, ldr, (hipStream_t)stream);
     });
 }

@@ -176,3 +176,44 @@ def test_sisso_batch_graph_replays_match_eager(torch, ctx, D):
                 assert bool((sub[b, d, 0, d + 1:] == -1).all())
                 assert np.array_equal(_bits(rmse[b, d, :1]), _bits(rd["rmse"][:1])), (b, d)
                 assert np.array_equal(_bits(coef[b, d, 0, :d + 2]), _bits(rd["coef"][0])), (b, d)
+
+
+def test_sisso_graph_omp_and_graph_timers(torch, ctx, D):
+    """discover_sisso_batch with OMP: the replayed graph gives the Python
+    loop's subspace, D-model and OMP extension (same rows, coefficients and
+    RMSE), and a kernel named for graph timing reports one timed launch per
+    replay while timing is on."""
+    rng = np.random.default_rng(91)
+    p, n = 7, 300
+    X = rng.uniform(0.5, 2.0, size=(p, n))
+    y = 0.3 + 1.5 * X[0] * X[1] - 0.8 * X[2] / X[3] + 0.4 * np.exp(-X[4]) + 0.01 * rng.normal(size=n)
+    Xd, yd = dev(torch, X), dev(torch, y)
+    prm = D.params(rung=2, k=20)
+    Dd, omp_D = 3, 6
+    ref = ctx.sisso(Xd, yd, prm, Dd, omp_D=omp_D)
+    S_ref = ref["S_ids"].cpu().numpy()
+    try:
+        ctx.set_graph_timing(["l0_sweep3"])
+        out = ctx.sisso_batch_graph([Xd], [yd], prm, Dd, omp_D=omp_D)
+        assert out[5] == 0
+        ctx.reset_timing()
+        ctx.set_timing(True)
+        for call in range(3):
+            out = ctx.sisso_batch_graph([Xd], [yd], prm, Dd, omp_D=omp_D)
+            assert out[5] == 1, (call, getattr(ctx, "capture_error", ""))
+            ids, sc, sub, rmse, coef, _, (oact, ocoef, ormse) = out
+            S_g = ids[0].reshape(-1).cpu().numpy()
+            assert np.array_equal(S_g, S_ref)
+            win = sorted(int(S_g[i]) for i in sub[0, Dd - 1, 0].cpu().numpy())
+            assert win == sorted(int(S_ref[i]) for i in ref["dims"][-1]["subsets"][0].cpu().numpy())
+            a_g = [int(S_g[i]) for i in oact[0].cpu().numpy()]
+            a_r = [int(S_ref[i]) for i in ref["omp"]["active"].cpu().numpy()]
+            assert a_g == a_r
+            np.testing.assert_allclose(ocoef[0].cpu().numpy(), ref["omp"]["coef"].cpu().numpy(),
+                                       rtol=1e-12, atol=0)
+            assert abs(float(ormse[0]) - float(ref["omp"]["rmse"])) <= 1e-12 * float(ref["omp"]["rmse"])
+        n_t, ms = ctx.timing("l0_sweep3")
+        assert n_t == 3 and ms > 0.0
+    finally:
+        ctx.set_timing(False)
+        ctx.set_graph_timing([])
