@@ -390,8 +390,8 @@ def main():
     ctx.set_timing(False)
     kern = {}
     for name in ("materialise", "screen_list", "screen_pairs", "screen_pairs_list", "select",
-                 "rescore", "sort_dedup", "dedup_pairs", "values", "l0_gram", "l0_table", "l0_sweep",
-                 "l0_sweep3", "l0_band", "l0_refit", "omp"):
+                 "rescore", "sort_dedup", "dedup_pairs", "groups", "values", "l0_gram", "l0_table",
+                 "l0_sweep", "l0_sweep3", "l0_band", "l0_refit", "omp"):
         n, t = ctx.timing(name)
         if n:
             kern[name] = {"launches_per_step": n / eager_steps, "ms_per_step": t / eager_steps,

@@ -1514,7 +1514,9 @@ __device__ __forceinline__ void d_rescore(const int64_t* __restrict__ pool,
                                                  double* __restrict__ ps,
                                                  uint8_t* __restrict__ pex,
                                                  const double* __restrict__ sc_row,
-                                                 unsigned long long* __restrict__ maxerr) {
+                                                 unsigned long long* __restrict__ maxerr,
+                                                 int32_t* __restrict__ rank,
+                                                 int32_t* __restrict__ order) {
     const int64_t P = min((int64_t)*Pp, cap);
     const int lane = threadIdx.x & 63;
     for (int64_t w = (int64_t)blockIdx.x * 4 + wave_id(); w < P; w += (int64_t)gridDim.x * 4) {
@@ -1539,6 +1541,8 @@ __device__ __forceinline__ void d_rescore(const int64_t* __restrict__ pool,
         }
         ps[w] = s;
         pex[w] = (uint8_t)ex;
+        rank[w] = 0;                                      // counted by k_rankp
+        order[w] = (int32_t)w;                            // (a valid index even before the scatter)
         const double x = sc_row[id];                      // screening-pass score
         if (s > 0.0 && x > 0.0)
             atomicMax(maxerr, (unsigned long long)__double_as_longlong(fabs(x - s)));
@@ -1583,75 +1587,123 @@ __device__ __forceinline__ void d_fixup(const int64_t* __restrict__ ids,
 }
 
 // Rank sort of the pool by (-score, ID).
-__device__ __forceinline__ void d_rank(const double* __restrict__ ps,
-                                              const int64_t* __restrict__ pool,
-                                              const unsigned long long* __restrict__ Pp, int64_t cap,
-                                              int32_t* __restrict__ order) {
-    const int64_t P = min((int64_t)*Pp, cap);
-    if (P <= 4096) return;                      // handled by k_bitonic
-    __shared__ double ts[1024];
-    __shared__ int64_t ti[1024];
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const double si = i < P ? ps[i] : 0.0;
-    const int64_t ii = i < P ? pool[i] : 0;
-    int64_t rank = 0;
-    for (int64_t base = 0; base < P; base += 1024) {
-        __syncthreads();
-        for (int k = threadIdx.x; k < 1024; k += 256) {
-            ts[k] = base + k < P ? ps[base + k] : -2.0;
-            ti[k] = base + k < P ? pool[base + k] : INT64_MAX;
+// Sort of the pool by (-score, ID) as ranks: entry i's sorted position is
+// the number of entries before it.  Blocks take a tile of 256 entries i and
+// a chunk of RCH entries j staged in LDS (grid-strided over both, so any
+// pool up to the capacity is covered) and add their counts with integer
+// atomics, so the ranks do not depend on the order the blocks run in.
+// Scores are -1 or positive (never NaN) and IDs are distinct, so the order
+// is total and the ranks are a permutation.
+constexpr int RCH = 256;
+
+// (score, ID) of one entry, staged in LDS as one 16-byte read; a tile of
+// them is scanned with a branch-free comparison, unrolled so that the LDS
+// reads of several entries are in flight together.
+struct __align__(16) SK {
+    double s;
+    long long id;
+};
+__device__ __forceinline__ int count_before(const SK* __restrict__ tile, int lim, double si, long long ii) {
+    int c = 0;
+    int j = 0;
+    for (; j + 8 <= lim; j += 8) {
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+            const SK e = tile[j + u];
+            c += (int)(e.s > si) | ((int)(e.s == si) & (int)(e.id < ii));
         }
-        __syncthreads();
-        const int lim = (int)min((int64_t)1024, P - base);
-        for (int k = 0; k < lim; k++) rank += (ts[k] > si) || (ts[k] == si && ti[k] < ii);
     }
-    if (i < P) order[rank] = (int32_t)i;
+    for (; j < lim; j++) {
+        const SK e = tile[j];
+        c += (int)(e.s > si) | ((int)(e.s == si) & (int)(e.id < ii));
+    }
+    return c;
+}
+
+__device__ __forceinline__ void d_rankp(const double* __restrict__ ps, const int64_t* __restrict__ pool,
+                                        const unsigned long long* __restrict__ Pp, int64_t cap,
+                                        int32_t* __restrict__ rank) {
+    const int64_t P = min((int64_t)*Pp, cap);
+    __shared__ SK tile[RCH];
+    for (int64_t j0 = (int64_t)blockIdx.y * RCH; j0 < P; j0 += (int64_t)gridDim.y * RCH) {
+        __syncthreads();
+        for (int q = threadIdx.x; q < RCH; q += 256)
+            tile[q] = j0 + q < P ? SK{ps[j0 + q], (long long)pool[j0 + q]} : SK{-2.0, INT64_MAX};
+        __syncthreads();
+        const int lim = (int)min((int64_t)RCH, P - j0);
+        for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i - threadIdx.x < P;
+             i += (int64_t)gridDim.x * 256) {
+            if (i >= P) continue;
+            const int c = count_before(tile, lim, ps[i], (long long)pool[i]);
+            if (c) atomicAdd(&rank[i], c);
+        }
+    }
+}
+
+// order[rank[i]] = i and the scores in sorted order.
+__device__ __forceinline__ void d_scatter(const double* __restrict__ ps,
+                                          const unsigned long long* __restrict__ Pp, int64_t cap,
+                                          const int32_t* __restrict__ rank, int32_t* __restrict__ order,
+                                          double* __restrict__ ss) {
+    const int64_t P = min((int64_t)*Pp, cap);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t r = rank[i];
+        order[r] = (int32_t)i;
+        ss[r] = ps[i];
+    }
 }
 
 // Near-tie window of each sorted entry: lo[q] = first earlier position whose
 // score is within TAU_NEAR (relative) of entry q, scanning backwards.
-__device__ __forceinline__ void d_window(const double* __restrict__ ps, const int32_t* __restrict__ order,
-                         const unsigned long long* __restrict__ Pp, int64_t cap,
-                         int32_t* __restrict__ lo, int32_t* __restrict__ cnt) {
+__device__ __forceinline__ void d_window(const double* __restrict__ ss,
+                                         const unsigned long long* __restrict__ Pp, int64_t cap,
+                                         int32_t* __restrict__ lo, int32_t* __restrict__ cnt) {
     const int64_t P = min((int64_t)*Pp, cap);
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < P;
          q += (int64_t)gridDim.x * blockDim.x) {
-    const double s = ps[order[q]];
-    int64_t l = q;
-    if (s > 0.0)
-        while (l > 0 && q - l < 1024) {
-            const double sp = ps[order[l - 1]];
-            if (!(sp - s <= TAU_NEAR * sp)) break;
-            l--;
-        }
-    lo[q] = (int32_t)l;
-    cnt[q] = (int32_t)(q - l);
+        const double s = ss[q];
+        int64_t l = q;
+        if (s > 0.0)
+            while (l > 0 && q - l < 1024) {
+                const double sp = ss[l - 1];
+                if (!(sp - s <= TAU_NEAR * sp)) break;
+                l--;
+            }
+        lo[q] = (int32_t)l;
+        cnt[q] = (int32_t)(q - l);
     }
 }
 
-// Exclusive prefix sum of cnt (single block).
+// Exclusive prefix sum of cnt (one block of 1024 threads): each thread sums
+// a contiguous chunk, the chunk sums are scanned across the block, then
+// each thread writes its chunk's offsets.
+__device__ __forceinline__ int64_t block_excl_scan1024(int64_t v, int64_t* part) {
+    const int t = threadIdx.x;
+    part[t] = v;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const int64_t x = t >= o ? part[t - o] : 0;
+        __syncthreads();
+        part[t] += x;
+        __syncthreads();
+    }
+    const int64_t incl = part[t];
+    __syncthreads();
+    return incl - v;
+}
+
 __device__ __forceinline__ void d_scan_offsets(const int32_t* __restrict__ cnt,
-                                                       const unsigned long long* __restrict__ Pp,
-                                                       int64_t cap, int64_t* __restrict__ off) {
+                                               const unsigned long long* __restrict__ Pp,
+                                               int64_t cap, int64_t* __restrict__ off) {
     const int64_t P = min((int64_t)*Pp, cap);
     __shared__ int64_t part[1024];
     const int64_t per = (P + 1023) / 1024;
     const int64_t b = threadIdx.x * per, e = min(P, b + per);
     int64_t s = 0;
     for (int64_t q = b; q < e; q++) s += cnt[q];
-    part[threadIdx.x] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int64_t acc = 0;
-        for (int k = 0; k < 1024; k++) {
-            const int64_t v = part[k];
-            part[k] = acc;
-            acc += v;
-        }
-        off[P] = acc;
-    }
-    __syncthreads();
-    int64_t acc = part[threadIdx.x];
+    int64_t acc = block_excl_scan1024(s, part);
+    if (threadIdx.x == 1023) off[P] = acc + s;
     for (int64_t q = b; q < e; q++) {
         off[q] = acc;
         acc += cnt[q];
@@ -1822,8 +1874,7 @@ __device__ __forceinline__ void d_groups(
     const int64_t ns = min((int64_t)k, nunb);
     // 5. representatives in (-score, ID) order (rank sort of <= k entries,
     // staged through LDS in tiles)
-    __shared__ double tsc[GRP_THREADS];
-    __shared__ int64_t tid_[GRP_THREADS];
+    __shared__ SK tile[GRP_THREADS];
     for (int64_t i0 = 0; i0 < ns; i0 += GRP_THREADS) {
         const int64_t i = i0 + t;
         double si = 0.0;
@@ -1838,14 +1889,11 @@ __device__ __forceinline__ void d_groups(
             __syncthreads();
             if (j0 + t < ns) {
                 const int32_t rq = reppos[headpos[j0 + t]];
-                tsc[t] = ps[order[rq]];
-                tid_[t] = pool[order[rq]];
+                tile[t] = SK{ps[order[rq]], (long long)pool[order[rq]]};
             }
             __syncthreads();
-            const int64_t lim = min((int64_t)GRP_THREADS, ns - j0);
-            if (i < ns)
-                for (int64_t j = 0; j < lim; j++)
-                    rank += (tsc[j] > si) || (tsc[j] == si && tid_[j] < ii);
+            const int lim = (int)min((int64_t)GRP_THREADS, ns - j0);
+            if (i < ns) rank += count_before(tile, lim, si, (long long)ii);
         }
         if (i < ns) {
             out_ids[rank] = ii;
@@ -1870,45 +1918,140 @@ __device__ __forceinline__ void d_groups(
     }
 }
 
-// Sort of a pool of at most 4096 entries by (-score, ID): bitonic network
-// in LDS, one block of 1024 threads.
-constexpr int BITONIC_MAX = 4096;
+// The same for a pool of at most GRP_LDS entries, with the group state in
+// LDS: parent (int32), the blocked flags (one bit per entry), and per head
+// the 64-bit minimum of (ID << 12 | position), which gives the
+// representative's ID and its sorted position at once (IDs stay below
+// 2^51).  The tiles of the final rank sort reuse the parent array.
+constexpr int GRP_LDS = 4096;
 
-__device__ __forceinline__ void d_bitonic(const double* __restrict__ ps,
-                                                  const int64_t* __restrict__ pool,
-                                                  const unsigned long long* __restrict__ Pp,
-                                                  int64_t cap, int32_t* __restrict__ order) {
-    const int64_t P = min((int64_t)*Pp, cap);
-    if (P > BITONIC_MAX) return;                // handled by k_rank
-    __shared__ double ks[BITONIC_MAX];
-    __shared__ int64_t ki[BITONIC_MAX];
-    __shared__ int32_t kx[BITONIC_MAX];
-    int N2 = 1;
-    while (N2 < P) N2 <<= 1;
-    for (int i = threadIdx.x; i < N2; i += 1024) {
-        ks[i] = i < P ? ps[i] : -INFINITY;
-        ki[i] = i < P ? pool[i] : INT64_MAX;
-        kx[i] = i;
+__device__ __forceinline__ void d_groups_lds(
+    const int64_t* __restrict__ pool, const double* __restrict__ ps, const uint8_t* __restrict__ pex,
+    const int32_t* __restrict__ order, const int32_t* __restrict__ lo, const int64_t* __restrict__ off,
+    const uint8_t* __restrict__ flag, int64_t P, int64_t flag_cap, int k, int dedup,
+    const uint32_t* __restrict__ sel, const int64_t* __restrict__ st, double margin,
+    int32_t* __restrict__ headpos, int64_t* __restrict__ out_ids, double* __restrict__ out_sc,
+    int64_t* __restrict__ res, int64_t total_flags) {
+    __shared__ int64_t part[GRP_THREADS];
+    __shared__ __align__(16) int32_t par[GRP_LDS];
+    __shared__ unsigned long long rkey[GRP_LDS];
+    __shared__ uint32_t blkb[GRP_LDS / 32];
+    __shared__ int changed, undecided;
+    const int t = threadIdx.x;
+    const bool all = st[1] != 0;
+    const double th_scan = all ? -1.0 : select_threshold(sel, st) - margin;
+    // 1. initial decisions
+    for (int q = t; q < P; q += GRP_THREADS) {
+        const double sq = ps[order[q]];
+        int32_t v = q;
+        if (!(sq > 0.0)) v = -3;                           // invalid after exact rescoring
+        else if (dedup) {
+            const int64_t o = off[q];
+            const int l = lo[q];
+            for (int p2 = l; p2 < q; p2++)
+                if (o + (p2 - l) < flag_cap && flag[o + (p2 - l)]) { v = -2; break; }
+        }
+        par[q] = v;
+        rkey[q] = ~0ull;
+    }
+    for (int w = t; w < GRP_LDS / 32; w += GRP_THREADS) blkb[w] = 0u;
+    __syncthreads();
+    // 2. rounds
+    for (;;) {
+        if (t == 0) { changed = 0; undecided = 0; }
+        __syncthreads();
+        for (int q = t; q < P; q += GRP_THREADS) {
+            if (par[q] != -2) continue;
+            int32_t dec = q;                               // head unless a flagged head comes first
+            bool wait = false;
+            const int64_t o = off[q];
+            const int l = lo[q];
+            for (int p2 = l; p2 < q; p2++) {
+                if (o + (p2 - l) >= flag_cap || !flag[o + (p2 - l)]) continue;
+                const int32_t sp2 = par[p2];
+                if (sp2 == -2) { wait = true; break; }
+                if (sp2 == p2) { dec = p2; break; }
+            }
+            if (wait) { atomicAdd(&undecided, 1); continue; }
+            par[q] = dec;
+            atomicAdd(&changed, 1);
+        }
+        __syncthreads();
+        const int ch = changed, un = undecided;
+        __syncthreads();
+        if (un == 0 || ch == 0) break;
+    }
+    // 3. aggregate groups onto their heads
+    int64_t merged_loc = 0;
+    for (int q = t; q < P; q += GRP_THREADS) {
+        const int32_t h = par[q];
+        if (h < 0) continue;
+        const int e = order[q];
+        if (pex[e]) atomicOr(&blkb[h >> 5], 1u << (h & 31));
+        atomicMin(&rkey[h], ((unsigned long long)pool[e] << 12) | (unsigned long long)q);
+        merged_loc += h != q;
     }
     __syncthreads();
-    for (int size = 2; size <= N2; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int u = threadIdx.x; u < N2 / 2; u += 1024) {
-                const int i = 2 * stride * (u / stride) + (u % stride);
-                const int j = i + stride;
-                const bool up = (i & size) == 0;
-                // "before(a, b)": a.s > b.s, ties by smaller ID
-                const bool jb = ks[j] > ks[i] || (ks[j] == ks[i] && ki[j] < ki[i]);
-                if (jb == up) {
-                    const double ts = ks[i]; ks[i] = ks[j]; ks[j] = ts;
-                    const int64_t ti = ki[i]; ki[i] = ki[j]; ki[j] = ti;
-                    const int32_t tx = kx[i]; kx[i] = kx[j]; kx[j] = tx;
-                }
+    // 4. rank the unblocked heads in sorted order (chunked block scan)
+    const int chunk = (int)((P + GRP_THREADS - 1) / GRP_THREADS);
+    const int q0 = t * chunk, q1 = (int)min(P, (int64_t)q0 + chunk);
+    auto unblocked_head = [&](int q) { return par[q] == q && !((blkb[q >> 5] >> (q & 31)) & 1u); };
+    int64_t cnt = 0;
+    for (int q = q0; q < q1; q++) cnt += unblocked_head(q);
+    int64_t r = block_excl_scan(cnt, part);
+    const int64_t nunb = part[GRP_THREADS - 1];
+    for (int q = q0; q < q1; q++)
+        if (unblocked_head(q)) {
+            if (r < k) headpos[r] = q;
+            r++;
+        }
+    block_excl_scan(merged_loc, part);
+    const int64_t merged_tot = part[GRP_THREADS - 1];
+    __syncthreads();
+    const int64_t ns = min((int64_t)k, nunb);
+    // 5. representatives in (-score, ID) order (rank sort of <= k entries,
+    // staged through LDS in tiles that reuse the parent array)
+    SK* tile = (SK*)par;                                          // 1024 entries = 16 KB
+    for (int64_t i0 = 0; i0 < ns; i0 += GRP_THREADS) {
+        const int64_t i = i0 + t;
+        double si = 0.0;
+        int64_t ii = 0;
+        if (i < ns) {
+            const unsigned long long kk = rkey[headpos[i]];
+            si = ps[order[(int)(kk & 4095ull)]];
+            ii = (int64_t)(kk >> 12);
+        }
+        int64_t rank = 0;
+        for (int64_t j0 = 0; j0 < ns; j0 += GRP_THREADS) {
+            __syncthreads();
+            if (j0 + t < ns) {
+                const unsigned long long kk = rkey[headpos[j0 + t]];
+                tile[t] = SK{ps[order[(int)(kk & 4095ull)]], (long long)(kk >> 12)};
             }
             __syncthreads();
+            const int lim = (int)min((int64_t)GRP_THREADS, ns - j0);
+            if (i < ns) rank += count_before(tile, lim, si, (long long)ii);
+        }
+        if (i < ns) {
+            out_ids[rank] = ii;
+            out_sc[rank] = si;
         }
     }
-    for (int i = threadIdx.x; i < P; i += 1024) order[i] = kx[i];
+    for (int64_t i = ns + t; i < k; i += GRP_THREADS) {
+        out_ids[i] = -1;
+        out_sc[i] = __longlong_as_double(0x7FF8000000000000LL);
+    }
+    if (t == 0) {
+        bool complete = all;
+        if (!all && nunb >= k) {
+            const double lim = ps[order[headpos[k - 1]]];
+            complete = (1.0 - TAU_NEAR) * lim >= th_scan;
+        }
+        res[0] = ns;
+        res[1] = complete ? 1 : 0;
+        res[2] = merged_tot;
+        res[3] = total_flags;                  // duplicate-check pairs (capacity check)
+    }
 }
 
 // Values of the selected candidates: one wave per output row.
@@ -1970,6 +2113,8 @@ struct SelArgs {
     uint8_t* pex;
     unsigned long long* maxerr;
     int32_t *order, *lo, *wc;
+    int32_t* rank;            // pool position -> sorted position (counted)
+    double* ss;               // scores in sorted order
     int64_t* off;
     uint8_t* flag;
     int32_t *parent, *blk;
@@ -1991,31 +2136,31 @@ __global__ __launch_bounds__(256) void k_rescore(ctab<SelArgs> A) {
     const SelArgs& a = tab(A, blockIdx.y);
     DSC_GLOBAL(a.sc); DSC_GLOBAL(a.sel); DSC_GLOBAL(a.st); DSC_GLOBAL(a.pool); DSC_GLOBAL(a.cnt); DSC_GLOBAL(a.ev.raw2c); DSC_GLOBAL(a.ev.valid); DSC_GLOBAL(a.o.Vf); DSC_GLOBAL(a.o.Rf); DSC_GLOBAL(a.Yc); DSC_GLOBAL(a.syy); DSC_GLOBAL(a.ps); DSC_GLOBAL(a.pex); DSC_GLOBAL(a.maxerr); DSC_GLOBAL(a.order); DSC_GLOBAL(a.lo); DSC_GLOBAL(a.wc); DSC_GLOBAL(a.off); DSC_GLOBAL(a.flag); DSC_GLOBAL(a.parent); DSC_GLOBAL(a.blk); DSC_GLOBAL(a.repid); DSC_GLOBAL(a.reppos); DSC_GLOBAL(a.headpos); DSC_GLOBAL(a.out_ids); DSC_GLOBAL(a.out_sc); DSC_GLOBAL(a.res);
     d_rescore<DISCOVER_MAX_TARGETS>(a.pool, a.cnt, a.cap, a.ev, a.o, a.n, a.T, a.mode, a.t, a.Yc, a.syy,
-                                    a.excl, a.n_excl, a.ps, a.pex, a.sc, a.maxerr);
+                                    a.excl, a.n_excl, a.ps, a.pex, a.sc, a.maxerr, a.rank, a.order);
 }
 
-__global__ __launch_bounds__(1024) void k_bitonic(ctab<SelArgs> A) {
-    const SelArgs& a = tab(A, blockIdx.x);
-    DSC_GLOBAL(a.sc); DSC_GLOBAL(a.sel); DSC_GLOBAL(a.st); DSC_GLOBAL(a.pool); DSC_GLOBAL(a.cnt); DSC_GLOBAL(a.ev.raw2c); DSC_GLOBAL(a.ev.valid); DSC_GLOBAL(a.o.Vf); DSC_GLOBAL(a.o.Rf); DSC_GLOBAL(a.Yc); DSC_GLOBAL(a.syy); DSC_GLOBAL(a.ps); DSC_GLOBAL(a.pex); DSC_GLOBAL(a.maxerr); DSC_GLOBAL(a.order); DSC_GLOBAL(a.lo); DSC_GLOBAL(a.wc); DSC_GLOBAL(a.off); DSC_GLOBAL(a.flag); DSC_GLOBAL(a.parent); DSC_GLOBAL(a.blk); DSC_GLOBAL(a.repid); DSC_GLOBAL(a.reppos); DSC_GLOBAL(a.headpos); DSC_GLOBAL(a.out_ids); DSC_GLOBAL(a.out_sc); DSC_GLOBAL(a.res);
-    d_bitonic(a.ps, a.pool, a.cnt, a.cap, a.order);
+// grid (i tiles, j chunks, lists)
+__global__ __launch_bounds__(256) void k_rankp(ctab<SelArgs> A) {
+    const SelArgs& a = tab(A, blockIdx.z);
+    DSC_GLOBAL(a.ps); DSC_GLOBAL(a.pool); DSC_GLOBAL(a.cnt); DSC_GLOBAL(a.rank); DSC_GLOBAL(a.order); DSC_GLOBAL(a.ss); DSC_GLOBAL(a.lo); DSC_GLOBAL(a.wc); DSC_GLOBAL(a.off);
+    d_rankp(a.ps, a.pool, a.cnt, a.cap, a.rank);
 }
 
-__global__ __launch_bounds__(256) void k_rank(ctab<SelArgs> A) {
+__global__ __launch_bounds__(256) void k_scatter(ctab<SelArgs> A) {
     const SelArgs& a = tab(A, blockIdx.y);
-    DSC_GLOBAL(a.sc); DSC_GLOBAL(a.sel); DSC_GLOBAL(a.st); DSC_GLOBAL(a.pool); DSC_GLOBAL(a.cnt); DSC_GLOBAL(a.ev.raw2c); DSC_GLOBAL(a.ev.valid); DSC_GLOBAL(a.o.Vf); DSC_GLOBAL(a.o.Rf); DSC_GLOBAL(a.Yc); DSC_GLOBAL(a.syy); DSC_GLOBAL(a.ps); DSC_GLOBAL(a.pex); DSC_GLOBAL(a.maxerr); DSC_GLOBAL(a.order); DSC_GLOBAL(a.lo); DSC_GLOBAL(a.wc); DSC_GLOBAL(a.off); DSC_GLOBAL(a.flag); DSC_GLOBAL(a.parent); DSC_GLOBAL(a.blk); DSC_GLOBAL(a.repid); DSC_GLOBAL(a.reppos); DSC_GLOBAL(a.headpos); DSC_GLOBAL(a.out_ids); DSC_GLOBAL(a.out_sc); DSC_GLOBAL(a.res);
-    if ((int64_t)blockIdx.x * 256 >= min((int64_t)*a.cnt, a.cap)) return;
-    d_rank(a.ps, a.pool, a.cnt, a.cap, a.order);
+    DSC_GLOBAL(a.ps); DSC_GLOBAL(a.pool); DSC_GLOBAL(a.cnt); DSC_GLOBAL(a.rank); DSC_GLOBAL(a.order); DSC_GLOBAL(a.ss); DSC_GLOBAL(a.lo); DSC_GLOBAL(a.wc); DSC_GLOBAL(a.off);
+    d_scatter(a.ps, a.cnt, a.cap, a.rank, a.order, a.ss);
 }
 
 __global__ __launch_bounds__(256) void k_window(ctab<SelArgs> A) {
     const SelArgs& a = tab(A, blockIdx.y);
-    DSC_GLOBAL(a.sc); DSC_GLOBAL(a.sel); DSC_GLOBAL(a.st); DSC_GLOBAL(a.pool); DSC_GLOBAL(a.cnt); DSC_GLOBAL(a.ev.raw2c); DSC_GLOBAL(a.ev.valid); DSC_GLOBAL(a.o.Vf); DSC_GLOBAL(a.o.Rf); DSC_GLOBAL(a.Yc); DSC_GLOBAL(a.syy); DSC_GLOBAL(a.ps); DSC_GLOBAL(a.pex); DSC_GLOBAL(a.maxerr); DSC_GLOBAL(a.order); DSC_GLOBAL(a.lo); DSC_GLOBAL(a.wc); DSC_GLOBAL(a.off); DSC_GLOBAL(a.flag); DSC_GLOBAL(a.parent); DSC_GLOBAL(a.blk); DSC_GLOBAL(a.repid); DSC_GLOBAL(a.reppos); DSC_GLOBAL(a.headpos); DSC_GLOBAL(a.out_ids); DSC_GLOBAL(a.out_sc); DSC_GLOBAL(a.res);
-    d_window(a.ps, a.order, a.cnt, a.cap, a.lo, a.wc);
+    DSC_GLOBAL(a.ps); DSC_GLOBAL(a.pool); DSC_GLOBAL(a.cnt); DSC_GLOBAL(a.rank); DSC_GLOBAL(a.order); DSC_GLOBAL(a.ss); DSC_GLOBAL(a.lo); DSC_GLOBAL(a.wc); DSC_GLOBAL(a.off);
+    d_window(a.ss, a.cnt, a.cap, a.lo, a.wc);
 }
 
 __global__ __launch_bounds__(1024) void k_scan_offsets(ctab<SelArgs> A) {
     const SelArgs& a = tab(A, blockIdx.x);
-    DSC_GLOBAL(a.sc); DSC_GLOBAL(a.sel); DSC_GLOBAL(a.st); DSC_GLOBAL(a.pool); DSC_GLOBAL(a.cnt); DSC_GLOBAL(a.ev.raw2c); DSC_GLOBAL(a.ev.valid); DSC_GLOBAL(a.o.Vf); DSC_GLOBAL(a.o.Rf); DSC_GLOBAL(a.Yc); DSC_GLOBAL(a.syy); DSC_GLOBAL(a.ps); DSC_GLOBAL(a.pex); DSC_GLOBAL(a.maxerr); DSC_GLOBAL(a.order); DSC_GLOBAL(a.lo); DSC_GLOBAL(a.wc); DSC_GLOBAL(a.off); DSC_GLOBAL(a.flag); DSC_GLOBAL(a.parent); DSC_GLOBAL(a.blk); DSC_GLOBAL(a.repid); DSC_GLOBAL(a.reppos); DSC_GLOBAL(a.headpos); DSC_GLOBAL(a.out_ids); DSC_GLOBAL(a.out_sc); DSC_GLOBAL(a.res);
+    DSC_GLOBAL(a.ps); DSC_GLOBAL(a.pool); DSC_GLOBAL(a.cnt); DSC_GLOBAL(a.rank); DSC_GLOBAL(a.order); DSC_GLOBAL(a.ss); DSC_GLOBAL(a.lo); DSC_GLOBAL(a.wc); DSC_GLOBAL(a.off);
     d_scan_offsets(a.wc, a.cnt, a.cap, a.off);
 }
 
@@ -2029,6 +2174,13 @@ __global__ __launch_bounds__(256) void k_pairs(ctab<SelArgs> A) {
 __global__ __launch_bounds__(GRP_THREADS) void k_groups(ctab<SelArgs> A) {
     const SelArgs& a = tab(A, blockIdx.x);
     DSC_GLOBAL(a.sc); DSC_GLOBAL(a.sel); DSC_GLOBAL(a.st); DSC_GLOBAL(a.pool); DSC_GLOBAL(a.cnt); DSC_GLOBAL(a.ev.raw2c); DSC_GLOBAL(a.ev.valid); DSC_GLOBAL(a.o.Vf); DSC_GLOBAL(a.o.Rf); DSC_GLOBAL(a.Yc); DSC_GLOBAL(a.syy); DSC_GLOBAL(a.ps); DSC_GLOBAL(a.pex); DSC_GLOBAL(a.maxerr); DSC_GLOBAL(a.order); DSC_GLOBAL(a.lo); DSC_GLOBAL(a.wc); DSC_GLOBAL(a.off); DSC_GLOBAL(a.flag); DSC_GLOBAL(a.parent); DSC_GLOBAL(a.blk); DSC_GLOBAL(a.repid); DSC_GLOBAL(a.reppos); DSC_GLOBAL(a.headpos); DSC_GLOBAL(a.out_ids); DSC_GLOBAL(a.out_sc); DSC_GLOBAL(a.res);
+    const int64_t P = min((int64_t)*a.cnt, a.cap);
+    if (P <= GRP_LDS) {
+        d_groups_lds(a.pool, a.ps, a.pex, a.order, a.lo, a.off, a.flag, P, a.fcap, a.k, a.dedup, a.sel,
+                     a.st, a.margin, a.headpos, a.out_ids, a.out_sc, a.res, P > 0 ? a.off[P] : 0);
+        if (threadIdx.x == 0) a.res[4] = (int64_t)*a.cnt;     // pool size (capacity check)
+        return;
+    }
     d_groups(a.pool, a.ps, a.pex, a.order, a.lo, a.off, a.flag, a.cnt, a.cap, a.fcap, a.k, a.dedup,
              a.sel, a.st, a.margin, a.parent, a.blk, a.repid, a.reppos, a.headpos, a.out_ids,
              a.out_sc, a.res);
@@ -2744,6 +2896,8 @@ static void select_round(discover_ctx* ctx, const discover_problem* probs,
         v.push_back(ar.add(cap * 4));              // order
         v.push_back(ar.add(cap * 4));              // lo
         v.push_back(ar.add(cap * 4));              // wc
+        v.push_back(ar.add(cap * 4));              // rank
+        v.push_back(ar.add(cap * 8));              // ss
         v.push_back(ar.add((cap + 1) * 8));        // off
         v.push_back(ar.add(fcap));                 // flag
         v.push_back(ar.add((cap + 1) * 4));        // parent
@@ -2759,7 +2913,7 @@ static void select_round(discover_ctx* ctx, const discover_problem* probs,
     sa.assign(nl, SelArgs{});
     std::vector<RadixArgs> ra(nl);
     std::vector<FillSeg> fills;
-    int64_t Nmax = 1, capmax = 1;
+    int64_t Nmax = 1, capmax = 1, Kmax = 1;
     for (int q = 0; q < nl; q++) {
         const ListState& L = LS[act[q]];
         const Problem& P = PS[L.b];
@@ -2770,6 +2924,7 @@ static void select_round(discover_ctx* ctx, const discover_problem* probs,
         auto at = [&](void) { return base + v[j++]; };
         a.pool = (int64_t*)at(); a.ps = (double*)at(); a.pex = (uint8_t*)at();
         a.order = (int32_t*)at(); a.lo = (int32_t*)at(); a.wc = (int32_t*)at();
+        a.rank = (int32_t*)at(); a.ss = (double*)at();
         a.off = (int64_t*)at(); a.flag = (uint8_t*)at();
         a.parent = (int32_t*)at(); a.blk = (int32_t*)at(); a.repid = (unsigned long long*)at();
         a.reppos = (int32_t*)at(); a.headpos = (int32_t*)at(); a.res = (int64_t*)at();
@@ -2792,6 +2947,7 @@ static void select_round(discover_ctx* ctx, const discover_problem* probs,
         fills.push_back(fill_seg(misc, 16, 0u));            // pool count, maximum error
         Nmax = std::max(Nmax, P.N);
         capmax = std::max(capmax, L.cap);
+        Kmax = std::max(Kmax, L.K);
     }
     fill_all(ctx, "sel_fills", fills, st);
     const ctab<SelArgs> dsa = ct(ctx->upload("sel_args", sa, st));
@@ -2810,8 +2966,11 @@ static void select_round(discover_ctx* ctx, const discover_problem* probs,
     }
     {
         KTimer kt(ctx, st, "sort_dedup");
-        k_bitonic<<<nl, 1024, 0, st>>>(dsa);
-        k_rank<<<dim3((unsigned)cdiv(capmax, 256), nl), 256, 0, st>>>(dsa);
+        // ranks over tiles of the expected pool size (grid-strided beyond it)
+        const unsigned ri = (unsigned)std::max<int64_t>(1, std::min<int64_t>(64, cdiv(Kmax + 256, 256)));
+        const unsigned rj = (unsigned)std::max<int64_t>(1, std::min<int64_t>(64, cdiv(Kmax + 256, RCH)));
+        k_rankp<<<dim3(ri, rj, nl), 256, 0, st>>>(dsa);
+        k_scatter<<<dim3((unsigned)std::min<int64_t>(1024, cdiv(capmax, 256)), nl), 256, 0, st>>>(dsa);
         k_window<<<dim3((unsigned)std::min<int64_t>(1024, cdiv(capmax, 256)), nl), 256, 0, st>>>(dsa);
         k_scan_offsets<<<nl, 1024, 0, st>>>(dsa);
         check_launch("k_sort");
@@ -2834,7 +2993,7 @@ static void select_reserve(discover_ctx* ctx, const discover_screen_params& prm,
     Arena ar;
     for (const ListState& L : LS) {
         const size_t cap = (size_t)L.cap, fcap = (size_t)L.fcap;
-        for (size_t b : {cap * 8, cap * 8, cap, cap * 4, cap * 4, cap * 4, (cap + 1) * 8, fcap,
+        for (size_t b : {cap * 8, cap * 8, cap, cap * 4, cap * 4, cap * 4, cap * 4, cap * 8, (cap + 1) * 8, fcap,
                          (cap + 1) * 4, (cap + 1) * 4, (cap + 1) * 8, (cap + 1) * 4,
                          ((size_t)prm.k + 1) * 4, (size_t)64, (size_t)64, (size_t)4096 * 4})
             ar.add(b);
