@@ -585,7 +585,10 @@ __device__ double block_sum256(double v, double* red) {
     return (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-__device__ void block_lsq(int n, int d, const int* idx, const double* __restrict__ F, int64_t ldf,
+// A may be LDS (dynamic shared memory) or a global slab: the function is
+// inlined into each caller's two branches, so each copy addresses its own
+// memory directly; the arithmetic is the same in both.
+__device__ __forceinline__ void block_lsq(int n, int d, const int* idx, const double* __restrict__ F, int64_t ldf,
                           const double* __restrict__ y, double* A, double* coef, double* rss,
                           double* resid) {
     __shared__ double red[4];
@@ -823,9 +826,11 @@ __global__ __launch_bounds__(256) void k_band_offsets(ctab<RefitArgs> A, int na,
 // spread over the whole GPU.
 __global__ __launch_bounds__(256) void k_refit_all(ctab<RefitArgs> A, int na,
                                                    const int64_t* __restrict__ boff,
-                                                   double* __restrict__ scratch, int64_t sld) {
+                                                   double* __restrict__ scratch, int64_t sld,
+                                                   int use_lds) {
     __shared__ double coef[DISCOVER_MAX_D + 1];
     __shared__ double rss;
+    extern __shared__ double dsm[];              // sld doubles when use_lds
     double* S = scratch + (int64_t)blockIdx.x * sld;
     const int64_t total = boff[na];
     for (int64_t e = blockIdx.x; e < total; e += gridDim.x) {
@@ -839,7 +844,8 @@ __global__ __launch_bounds__(256) void k_refit_all(ctab<RefitArgs> A, int na,
         const int64_t le = e - boff[lo];
         const int4 s = a.band[le];
         const int idx[3] = {s.x, s.y, s.z};
-        block_lsq(a.n, a.D, idx, a.F, a.ldf, a.y, S, coef, &rss, nullptr);
+        if (use_lds) block_lsq(a.n, a.D, idx, a.F, a.ldf, a.y, dsm, coef, &rss, nullptr);
+        else block_lsq(a.n, a.D, idx, a.F, a.ldf, a.y, S, coef, &rss, nullptr);
         if (threadIdx.x == 0) {
             a.brss[le] = rss;
             for (int j = 0; j <= a.D; j++) a.bcoef[le * (a.D + 1) + j] = coef[j];
@@ -929,14 +935,17 @@ __global__ __launch_bounds__(256) void k_omp_fit(int n, const double* __restrict
                                                  const int32_t* __restrict__ active,
                                                  const int32_t* __restrict__ nact,
                                                  double* __restrict__ A, double* __restrict__ coef,
-                                                 double* __restrict__ rss, double* __restrict__ r) {
+                                                 double* __restrict__ rss, double* __restrict__ r,
+                                                 int use_lds) {
     __shared__ int idx[DISCOVER_MAX_D];
     __shared__ double cf[DISCOVER_MAX_D + 1];
     __shared__ double rs;
+    extern __shared__ double dsm[];              // (D_max + 2) * n doubles when use_lds
     const int d = *nact;
     if (threadIdx.x < d) idx[threadIdx.x] = active[threadIdx.x];
     __syncthreads();
-    block_lsq(n, d, idx, F, ldf, y, A, cf, &rs, r);
+    if (use_lds) block_lsq(n, d, idx, F, ldf, y, dsm, cf, &rs, r);
+    else block_lsq(n, d, idx, F, ldf, y, A, cf, &rs, r);
     if (threadIdx.x == 0) {
         for (int j = 0; j <= d; j++) coef[j] = cf[j];
         *rss = rs;
@@ -1265,7 +1274,9 @@ void l0_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D
         {
             KTimer kt(ctx, st, "l0_refit");
             k_band_offsets<<<1, 256, 0, st>>>(dfa, na, boff);
-            k_refit_all<<<NREFIT, 256, 0, st>>>(dfa, na, boff, rscratch, sld);
+            const int rl = sld * (int64_t)sizeof(double) <= 65536 ? 1 : 0;   // QR columns in LDS
+            k_refit_all<<<NREFIT, 256, rl ? (size_t)sld * sizeof(double) : 0, st>>>(dfa, na, boff, rscratch,
+                                                                                   sld, rl);
             check_launch("k_refit");
         }
         k_rank_models<<<na, 64, 0, st>>>(dfa);
@@ -1382,12 +1393,17 @@ void omp_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int 
         k_row_norm<<<(unsigned)cdiv(pb.S, 4), 256, 0, st>>>(pb.S, ldz, Z, pb.n, nrm);
         k_omp_init<<<1, 64, 0, st>>>(active, D_max, n_init ? init_active + (int64_t)b * init_ld : nullptr,
                                      n_init, pb.S, nact);
-        k_omp_fit<<<1, 256, 0, st>>>(pb.n, pb.F, pb.ldf, pb.y, active, nact, A, coef, rss, r);
+        // the QR's columns in LDS when they fit in 64 KB
+        const size_t qr_bytes = (size_t)(D_max + 2) * pb.n * sizeof(double);
+        const int qr_lds = qr_bytes <= 65536 ? 1 : 0;
+        const size_t dyn = qr_lds ? qr_bytes : 0;
+        k_omp_fit<<<1, 256, dyn, st>>>(pb.n, pb.F, pb.ldf, pb.y, active, nact, A, coef, rss, r, qr_lds);
         for (int step = n_init; step < D_max; step++) {
             k_omp_corr<<<(unsigned)cdiv(pb.S, 4), 256, 0, st>>>(pb.n, pb.S, Z, ldz, r, active,
                                                                 nact, g);
             k_omp_pick<<<1, 256, 0, st>>>(pb.S, g, pb.ids, nrm, active, nact);
-            k_omp_fit<<<1, 256, 0, st>>>(pb.n, pb.F, pb.ldf, pb.y, active, nact, A, coef, rss, r);
+            k_omp_fit<<<1, 256, dyn, st>>>(pb.n, pb.F, pb.ldf, pb.y, active, nact, A, coef, rss, r,
+                                           qr_lds);
         }
         k_omp_rmse<<<1, 64, 0, st>>>(rss, pb.n, out_rmse + b);
         check_launch("omp");
