@@ -144,6 +144,12 @@ struct SweepArgs {
     double* lane_q;           // [n_items][64] (D = 1, 2) or [n_items][256] (D = 3)
     int64_t item0;            // first merged block (D = 3) or merged block of 4 waves (D = 1, 2)
     const double* theta;      // D = 3: the bound th of the table's shifted Q_ab
+    // bounded D = 3: lanes holding a value (a subset above th) are listed
+    // here instead of writing every lane: lane index within lane_q's
+    // layout, value; capacity = every lane, count zeroed by k_sw3_theta
+    int32_t* lidx;
+    double* lval;
+    unsigned long long* lcnt;
 };
 
 __device__ __forceinline__ double fast_rcp(double x) {
@@ -374,7 +380,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
     const int c = c0 + lane;
     double* out = g.lane_q + (li * 4 + wv) * (SW3_A * 64);
     if (a0 < 0) {                                        // padding block (uniform)
-        for (int k = 0; k < SW3_A; k++) out[k * 64 + lane] = -1.0;
+        // (the bounded form lists lanes instead; its lane_q holds the list)
+        if (!BOUND)
+            for (int k = 0; k < SW3_A; k++) out[k * 64 + lane] = -1.0;
         return;
     }
     const double th = *g.theta;
@@ -398,8 +406,34 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
     // b < c0: every lane has c > b; from c0 on, lanes with c <= b are cut
     sw3_run<false, BOUND>(Ew, g.lde, g.G, g.ldg, (uint32_t)cc, c0, bstart, min(bend, c0), th, L, low);
     sw3_run<true, BOUND>(Ew, g.lde, g.G, g.ldg, (uint32_t)cc, c0, max(bstart, c0), bend, th, L, low);
+    if (!BOUND) {
 #pragma unroll
-    for (int k = 0; k < SW3_A; k++) out[k * 64 + lane] = cok ? -low[k] : -1.0;   // -1: no valid triple
+        for (int k = 0; k < SW3_A; k++) out[k * 64 + lane] = cok ? -low[k] : -1.0;   // -1: no valid triple
+        return;
+    }
+    // bounded: append the lanes that hold a value (one atomic per wave)
+    uint64_t keep[SW3_A];
+    int tot = 0;
+#pragma unroll
+    for (int k = 0; k < SW3_A; k++) {
+        keep[k] = __builtin_amdgcn_ballot_w64(cok && low[k] < 0.5);
+        tot += __popcll(keep[k]);
+    }
+    if (tot == 0) return;                               // (wave-uniform)
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(g.lcnt, (unsigned long long)tot);
+    base = __shfl(base, 0, 64);
+    const uint64_t below = (1ull << lane) - 1ull;
+    const int64_t lane0 = (li * 4 + wv) * (SW3_A * 64);
+#pragma unroll
+    for (int k = 0; k < SW3_A; k++) {
+        if ((keep[k] >> lane) & 1ull) {
+            const unsigned long long pos = base + __popcll(keep[k] & below);
+            g.lidx[pos] = (int32_t)(lane0 + k * 64 + lane);
+            g.lval[pos] = -low[k];
+        }
+        base += __popcll(keep[k]);
+    }
 }
 
 // Lower bound for the bounded sweep, step 1: one wave per row a.  b(a) is
@@ -411,6 +445,7 @@ struct ThetaArgs {
     int ldg, S;
     double* rowq;
     double* theta;
+    unsigned long long* lcnt;     // the bounded sweep's lane-list count, zeroed here
 };
 
 __device__ __forceinline__ void wave_argmax(double& v, int& i) {
@@ -465,7 +500,7 @@ __global__ __launch_bounds__(256) void k_sw3_rows(ctab<ThetaArgs> A) {
 // subset passes the bounded test).
 __global__ __launch_bounds__(256) void k_sw3_theta(ctab<ThetaArgs> A, int m) {
     const ThetaArgs& g = tab(A, blockIdx.x);
-    DSC_GLOBAL(g.rowq); DSC_GLOBAL(g.theta);
+    DSC_GLOBAL(g.rowq); DSC_GLOBAL(g.theta); DSC_GLOBAL(g.lcnt);
     __shared__ double sv[4];
     __shared__ int si[4];
     double pv = __builtin_inf();
@@ -487,7 +522,10 @@ __global__ __launch_bounds__(256) void k_sw3_theta(ctab<ThetaArgs> A, int m) {
             if (sv[w] > v || (sv[w] == v && si[w] < i)) { v = sv[w]; i = si[w]; }
         pv = v; pi = i;
     }
-    if (threadIdx.x == 0) *g.theta = pv >= 0.0 ? pv - SW3_TH_SLACK : -1.0;
+    if (threadIdx.x == 0) {
+        *g.theta = pv >= 0.0 ? pv - SW3_TH_SLACK : -1.0;
+        *g.lcnt = 0;
+    }
 }
 
 // Band expansion.  thr = (m-th best lane value) * (1 - 1e-12) - GRAM_DELTA.
@@ -509,6 +547,9 @@ struct BandArgs {
     unsigned long long* pcnt;
     int64_t pcap;
     const double* theta;      // D = 3: the table's shift th
+    const int32_t* lidx;      // bounded D = 3: listed lanes (lane index, value) instead of lane_q
+    const double* lval;
+    const unsigned long long* lcnt;
 };
 
 // For D = 3 the lane values carry the sweep's reciprocal error (at most
@@ -530,12 +571,13 @@ __device__ __forceinline__ void band_push(const BandArgs& g, int a, int b, int c
 // grid (blocks, problems)
 __global__ __launch_bounds__(256) void k_band_lanes(ctab<BandArgs> A) {
     const BandArgs& g = tab(A, blockIdx.y);
-    DSC_GLOBAL(g.lane_q); DSC_GLOBAL(g.items); DSC_GLOBAL(g.items3); DSC_GLOBAL(g.sel); DSC_GLOBAL(g.st); DSC_GLOBAL(g.band); DSC_GLOBAL(g.bcnt); DSC_GLOBAL(g.pairs); DSC_GLOBAL(g.pcnt);
+    DSC_GLOBAL(g.lane_q); DSC_GLOBAL(g.items); DSC_GLOBAL(g.items3); DSC_GLOBAL(g.sel); DSC_GLOBAL(g.st); DSC_GLOBAL(g.band); DSC_GLOBAL(g.bcnt); DSC_GLOBAL(g.pairs); DSC_GLOBAL(g.pcnt); DSC_GLOBAL(g.lidx); DSC_GLOBAL(g.lval); DSC_GLOBAL(g.lcnt);
     const double thr = band_thr(g);
     const int per = g.D == 3 ? 4 * SW3_A * 64 : 64;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < g.n_lanes;
-         i += (int64_t)gridDim.x * 256) {
-        const double q = g.lane_q[i];
+    const int64_t nl = g.lidx ? min((int64_t)*g.lcnt, g.n_lanes) : g.n_lanes;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < nl; e += (int64_t)gridDim.x * 256) {
+        const int64_t i = g.lidx ? (int64_t)g.lidx[e] : e;
+        const double q = g.lidx ? g.lval[e] : g.lane_q[i];
         if (!(q > -0.5) || q < thr - (g.D == 3 ? SW3_RCP_DELTA : 0.0) - 1e-9) continue;
         const int lane = (int)(i % per);
         if (g.D == 1) band_push(g, g.items[i / per].y + lane, -1, -1);
@@ -1119,6 +1161,7 @@ void l0_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D
         v.push_back(ar.add(D == 3 ? (size_t)pb.S * a.lde * 32 : 32));      // E
         v.push_back(ar.add(8));                                            // th
         v.push_back(ar.add(D == 3 ? (size_t)pb.S * 8 : 8));                // row values
+        v.push_back(ar.add(8));                                            // lane-list count
         Smax = std::max(Smax, pb.S);
         ldemax = std::max(ldemax, a.lde);
         if (D == 3) tot_items3 += ni[b]; else tot_items += ni[b];
@@ -1147,7 +1190,7 @@ void l0_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D
             std::vector<ThetaArgs> ta(nb);
             for (int b = 0; b < nb; b++)
                 ta[b] = ThetaArgs{pa[b].G, pa[b].ldg, probs[b].S, (double*)(base + o[b][5]),
-                                  (double*)(base + o[b][4])};
+                                  (double*)(base + o[b][4]), (unsigned long long*)(base + o[b][6])};
             const ctab<ThetaArgs> dta = ct(ctx->upload("l0_theta", ta, st));
             k_sw3_rows<<<dim3((unsigned)cdiv(Smax, 4), nb), 256, 0, st>>>(dta);
             k_sw3_theta<<<nb, 256, 0, st>>>(dta, m);
@@ -1174,6 +1217,8 @@ void l0_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D
     const int4* d_items3 = D == 3 ? ctx->upload("l0_items3", items3, st) : nullptr;
     const int* d_bprob = ctx->upload("l0_bprob", bprob, st);
     double* lane_q = ctx->buf<double>("l0_laneq", (size_t)tot_lanes);
+    // bounded D = 3: listed lanes (indices here, values in lane_q's slice)
+    int32_t* lane_idx = bound ? ctx->buf<int32_t>("l0_laneidx", (size_t)tot_lanes) : nullptr;
     std::vector<SweepArgs> sa(nb);
     for (int b = 0; b < nb; b++) {
         SweepArgs& g = sa[b];
@@ -1185,6 +1230,11 @@ void l0_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D
         g.lane_q = lane_q + lane0[b];
         g.item0 = blk0[b];
         g.theta = pa[b].theta;
+        if (bound) {
+            g.lidx = lane_idx + lane0[b];
+            g.lval = g.lane_q;
+            g.lcnt = (unsigned long long*)(base + o[b][6]);
+        }
     }
     const ctab<SweepArgs> dsa = ct(ctx->upload("l0_sweep", sa, st));
     {
@@ -1243,8 +1293,9 @@ void l0_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D
             g.band = (int4*)(bb + v[0]); g.bcnt = (unsigned long long*)misc; g.bcap = cap[b];
             g.pairs = (int4*)(bb + v[1]); g.pcnt = (unsigned long long*)misc + 1; g.pcap = cap[b];
             g.theta = pa[b].theta;
-            ra[q] = RadixArgs{g.lane_q, g.n_lanes, m, (uint32_t*)(bb + v[7]), (uint32_t*)(misc + 32),
-                              (int64_t*)(misc + 16)};
+            g.lidx = sa[b].lidx; g.lval = sa[b].lval; g.lcnt = sa[b].lcnt;
+            ra[q] = RadixArgs{g.lidx ? g.lval : g.lane_q, g.n_lanes, m, (uint32_t*)(bb + v[7]),
+                              (uint32_t*)(misc + 32), (int64_t*)(misc + 16), g.lidx ? g.lcnt : nullptr};
             fills.push_back(fill_seg(misc, 16, 0u));
             lanes_max = std::max(lanes_max, g.n_lanes);
             RefitArgs& f = fa[q];
@@ -1264,9 +1315,11 @@ void l0_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D
         const ctab<RefitArgs> dfa = ct(ctx->upload("l0_refit", fa, st));
         {
             KTimer kt(ctx, st, "l0_band");
-            radix_select(dra, na, lanes_max, st);
+            // the bounded sweep's lane lists are short: fewer blocks (grid-strided)
+            const int64_t scan = bound ? std::min<int64_t>(lanes_max, 1 << 16) : lanes_max;
+            radix_select(dra, na, scan, st);
             const unsigned lb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(std::max(8, 1024 / na),
-                                                                                cdiv(lanes_max, 256)));
+                                                                                cdiv(scan, 256)));
             k_band_lanes<<<dim3(lb, na), 256, 0, st>>>(dba);
             if (D == 3) k_band_expand3<<<dim3((unsigned)std::max(8, 1024 / na), na), 256, 0, st>>>(dba);
             check_launch("k_band");

@@ -2943,7 +2943,7 @@ static void select_round(discover_ctx* ctx, const discover_problem* probs,
         a.excl = pb.exclude; a.n_excl = pb.exclude ? pb.n_exclude : 0;
         a.out_ids = outs[L.b].ids + (int64_t)L.t * k;
         a.out_sc = outs[L.b].sc + (int64_t)L.t * k;
-        ra[q] = RadixArgs{a.sc, P.N, L.K, hist, sel, stv};
+        ra[q] = RadixArgs{a.sc, P.N, L.K, hist, sel, stv, nullptr};
         fills.push_back(fill_seg(misc, 16, 0u));            // pool count, maximum error
         Nmax = std::max(Nmax, P.N);
         capmax = std::max(capmax, L.cap);

@@ -29,6 +29,7 @@ struct RadixArgs {
     uint32_t* hist;
     uint32_t* sel;
     int64_t* st;
+    const unsigned long long* Nd;   // or NULL: device count of entries (at most N)
 };
 
 static __global__ __launch_bounds__(256) void k_radix_init(ctab<RadixArgs> A) {
@@ -45,7 +46,7 @@ static __global__ __launch_bounds__(256) void k_radix_init(ctab<RadixArgs> A) {
 // grid (blocks, lists)
 static __global__ __launch_bounds__(256) void k_hist(ctab<RadixArgs> A, int level) {
     const RadixArgs& a = tab(A, blockIdx.y);
-    DSC_GLOBAL(a.x); DSC_GLOBAL(a.hist); DSC_GLOBAL(a.sel);
+    DSC_GLOBAL(a.x); DSC_GLOBAL(a.hist); DSC_GLOBAL(a.sel); DSC_GLOBAL(a.Nd);
     __shared__ uint32_t h[4096];
     for (int b = threadIdx.x; b < 4096; b += 256) h[b] = 0;
     __syncthreads();
@@ -53,7 +54,7 @@ static __global__ __launch_bounds__(256) void k_hist(ctab<RadixArgs> A, int leve
     if (level > 0) p0 = a.sel[0];
     if (level > 1) p1 = a.sel[1];
     const double* __restrict__ sc = a.x;
-    const int64_t N = a.N;
+    const int64_t N = a.Nd ? min((int64_t)*a.Nd, a.N) : a.N;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256) {
         const double x = sc[i];
         if (!(x > 0.0)) continue;
