@@ -1491,11 +1491,21 @@ __device__ __forceinline__ void d_compact(const double* __restrict__ sc, int64_t
                                                  unsigned long long* __restrict__ cnt) {
     const double th = select_threshold(sel, st);
     const double lo = st[1] ? 0.0 : th - 2.0 * margin;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256) {
-        const double x = sc[i];
+    // one atomic per wave: lanes take consecutive slots in lane order
+    const int lane = threadIdx.x & 63;
+    const uint64_t below = (1ull << lane) - 1ull;
+    for (int64_t i0 = (int64_t)blockIdx.x * 256 + (threadIdx.x & ~63); i0 < N;
+         i0 += (int64_t)gridDim.x * 256) {
+        const int64_t i = i0 + lane;
+        const double x = i < N ? sc[i] : 0.0;
         const bool take = (x > 0.0 && x >= lo) || (x < 0.0 && -x >= lo);
+        const uint64_t m = __builtin_amdgcn_ballot_w64(take);
+        if (!m) continue;                                 // (wave-uniform)
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(cnt, (unsigned long long)__popcll(m));
+        base = __shfl(base, 0, 64);
         if (take) {
-            const unsigned long long slot = atomicAdd(cnt, 1ull);
+            const unsigned long long slot = base + __popcll(m & below);
             if ((int64_t)slot < cap) pool[slot] = i;
         }
     }
@@ -1514,7 +1524,7 @@ __device__ __forceinline__ void d_rescore(const int64_t* __restrict__ pool,
                                                  double* __restrict__ ps,
                                                  uint8_t* __restrict__ pex,
                                                  const double* __restrict__ sc_row,
-                                                 unsigned long long* __restrict__ maxerr,
+                                                 double* __restrict__ perr,
                                                  int32_t* __restrict__ rank,
                                                  int32_t* __restrict__ order) {
     const int64_t P = min((int64_t)*Pp, cap);
@@ -1544,8 +1554,7 @@ __device__ __forceinline__ void d_rescore(const int64_t* __restrict__ pool,
         rank[w] = 0;                                      // counted by k_rankp
         order[w] = (int32_t)w;                            // (a valid index even before the scatter)
         const double x = sc_row[id];                      // screening-pass score
-        if (s > 0.0 && x > 0.0)
-            atomicMax(maxerr, (unsigned long long)__double_as_longlong(fabs(x - s)));
+        perr[w] = s > 0.0 && x > 0.0 ? fabs(x - s) : 0.0; // its maximum is taken by k_groups
     }
     }
 }
@@ -2115,6 +2124,7 @@ struct SelArgs {
     int32_t *order, *lo, *wc;
     int32_t* rank;            // pool position -> sorted position (counted)
     double* ss;               // scores in sorted order
+    double* perr;             // |screening score - exact score| per pool entry
     int64_t* off;
     uint8_t* flag;
     int32_t *parent, *blk;
@@ -2136,7 +2146,7 @@ __global__ __launch_bounds__(256) void k_rescore(ctab<SelArgs> A) {
     const SelArgs& a = tab(A, blockIdx.y);
     DSC_GLOBAL(a.sc); DSC_GLOBAL(a.sel); DSC_GLOBAL(a.st); DSC_GLOBAL(a.pool); DSC_GLOBAL(a.cnt); DSC_GLOBAL(a.ev.raw2c); DSC_GLOBAL(a.ev.valid); DSC_GLOBAL(a.o.Vf); DSC_GLOBAL(a.o.Rf); DSC_GLOBAL(a.Yc); DSC_GLOBAL(a.syy); DSC_GLOBAL(a.ps); DSC_GLOBAL(a.pex); DSC_GLOBAL(a.maxerr); DSC_GLOBAL(a.order); DSC_GLOBAL(a.lo); DSC_GLOBAL(a.wc); DSC_GLOBAL(a.off); DSC_GLOBAL(a.flag); DSC_GLOBAL(a.parent); DSC_GLOBAL(a.blk); DSC_GLOBAL(a.repid); DSC_GLOBAL(a.reppos); DSC_GLOBAL(a.headpos); DSC_GLOBAL(a.out_ids); DSC_GLOBAL(a.out_sc); DSC_GLOBAL(a.res);
     d_rescore<DISCOVER_MAX_TARGETS>(a.pool, a.cnt, a.cap, a.ev, a.o, a.n, a.T, a.mode, a.t, a.Yc, a.syy,
-                                    a.excl, a.n_excl, a.ps, a.pex, a.sc, a.maxerr, a.rank, a.order);
+                                    a.excl, a.n_excl, a.ps, a.pex, a.sc, a.perr, a.rank, a.order);
 }
 
 // grid (i tiles, j chunks, lists)
@@ -2175,6 +2185,20 @@ __global__ __launch_bounds__(GRP_THREADS) void k_groups(ctab<SelArgs> A) {
     const SelArgs& a = tab(A, blockIdx.x);
     DSC_GLOBAL(a.sc); DSC_GLOBAL(a.sel); DSC_GLOBAL(a.st); DSC_GLOBAL(a.pool); DSC_GLOBAL(a.cnt); DSC_GLOBAL(a.ev.raw2c); DSC_GLOBAL(a.ev.valid); DSC_GLOBAL(a.o.Vf); DSC_GLOBAL(a.o.Rf); DSC_GLOBAL(a.Yc); DSC_GLOBAL(a.syy); DSC_GLOBAL(a.ps); DSC_GLOBAL(a.pex); DSC_GLOBAL(a.maxerr); DSC_GLOBAL(a.order); DSC_GLOBAL(a.lo); DSC_GLOBAL(a.wc); DSC_GLOBAL(a.off); DSC_GLOBAL(a.flag); DSC_GLOBAL(a.parent); DSC_GLOBAL(a.blk); DSC_GLOBAL(a.repid); DSC_GLOBAL(a.reppos); DSC_GLOBAL(a.headpos); DSC_GLOBAL(a.out_ids); DSC_GLOBAL(a.out_sc); DSC_GLOBAL(a.res);
     const int64_t P = min((int64_t)*a.cnt, a.cap);
+    {
+        // maximum |screening - exact| over the pool (one atomic per list)
+        __shared__ double emax[GRP_THREADS / 64];
+        double e = 0.0;
+        for (int64_t q = threadIdx.x; q < P; q += GRP_THREADS) e = fmax(e, a.perr[q]);
+        e = wave_max(e);
+        if ((threadIdx.x & 63) == 0) emax[threadIdx.x >> 6] = e;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int w = 1; w < GRP_THREADS / 64; w++) e = fmax(e, emax[w]);
+            if (e > 0.0) atomicMax(a.maxerr, (unsigned long long)__double_as_longlong(e));
+        }
+        __syncthreads();
+    }
     if (P <= GRP_LDS) {
         d_groups_lds(a.pool, a.ps, a.pex, a.order, a.lo, a.off, a.flag, P, a.fcap, a.k, a.dedup, a.sel,
                      a.st, a.margin, a.headpos, a.out_ids, a.out_sc, a.res, P > 0 ? a.off[P] : 0);
@@ -2898,6 +2922,7 @@ static void select_round(discover_ctx* ctx, const discover_problem* probs,
         v.push_back(ar.add(cap * 4));              // wc
         v.push_back(ar.add(cap * 4));              // rank
         v.push_back(ar.add(cap * 8));              // ss
+        v.push_back(ar.add(cap * 8));              // perr
         v.push_back(ar.add((cap + 1) * 8));        // off
         v.push_back(ar.add(fcap));                 // flag
         v.push_back(ar.add((cap + 1) * 4));        // parent
@@ -2924,7 +2949,7 @@ static void select_round(discover_ctx* ctx, const discover_problem* probs,
         auto at = [&](void) { return base + v[j++]; };
         a.pool = (int64_t*)at(); a.ps = (double*)at(); a.pex = (uint8_t*)at();
         a.order = (int32_t*)at(); a.lo = (int32_t*)at(); a.wc = (int32_t*)at();
-        a.rank = (int32_t*)at(); a.ss = (double*)at();
+        a.rank = (int32_t*)at(); a.ss = (double*)at(); a.perr = (double*)at();
         a.off = (int64_t*)at(); a.flag = (uint8_t*)at();
         a.parent = (int32_t*)at(); a.blk = (int32_t*)at(); a.repid = (unsigned long long*)at();
         a.reppos = (int32_t*)at(); a.headpos = (int32_t*)at(); a.res = (int64_t*)at();
@@ -2961,7 +2986,15 @@ static void select_round(discover_ctx* ctx, const discover_problem* probs,
     check_launch("k_compact");
     {
         KTimer kt(ctx, st, "rescore");
+#ifndef RESCORE_GRID
+#define RESCORE_GRID 0
+#endif
+#if RESCORE_GRID == 0
         k_rescore<<<dim3((unsigned)std::min<int64_t>(std::max(64, 2048 / nl), cdiv(capmax, 4)), nl), 256, 0, st>>>(dsa);
+#else
+        // one wave per expected pool entry (grid-strided beyond)
+        k_rescore<<<dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(Kmax + 64, 4), cdiv(capmax, 4))), nl), 256, 0, st>>>(dsa);
+#endif
         check_launch("k_rescore");
     }
     {
@@ -2993,7 +3026,7 @@ static void select_reserve(discover_ctx* ctx, const discover_screen_params& prm,
     Arena ar;
     for (const ListState& L : LS) {
         const size_t cap = (size_t)L.cap, fcap = (size_t)L.fcap;
-        for (size_t b : {cap * 8, cap * 8, cap, cap * 4, cap * 4, cap * 4, cap * 4, cap * 8, (cap + 1) * 8, fcap,
+        for (size_t b : {cap * 8, cap * 8, cap, cap * 4, cap * 4, cap * 4, cap * 4, cap * 8, cap * 8, (cap + 1) * 8, fcap,
                          (cap + 1) * 4, (cap + 1) * 4, (cap + 1) * 8, (cap + 1) * 4,
                          ((size_t)prm.k + 1) * 4, (size_t)64, (size_t)64, (size_t)4096 * 4})
             ar.add(b);
