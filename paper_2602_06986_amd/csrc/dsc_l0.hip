@@ -216,7 +216,7 @@ __global__ __launch_bounds__(256) void k_sweep2(ctab<SweepArgs> A, const int* __
 // Bounded sweep.  Before the sweep, a lower bound theta on the m-th best
 // subset is taken from m subsets in distinct lanes (k_sw3_rows/k_sw3_theta)
 // and lowered by every allowance of the band (th = theta - GRAM_DELTA -
-// 4 SW3_RCP_DELTA - 1e-8).  The table stores Q_ab - th, so the test
+// 4 SW3_RCP_DELTA - 2^-24 - 1e-8).  The table stores Q_ab - th, so the test
 //   e^2 + (Q_ab - th) den > 0   <=>   q > th      (den > 0)
 // costs one FMA and two 32-bit compares per subset; only when some lane of
 // the wave passes it are the wave's exact values (reciprocal, pivot test,
@@ -224,12 +224,14 @@ __global__ __launch_bounds__(256) void k_sweep2(ctab<SweepArgs> A, const int* __
 // reports that subset's exact sweep value, as an unbounded sweep would, and
 // every other lane reports a value below th (or -1), which no band
 // threshold can reach: the m lanes that define theta report at least theta,
-// so the threshold is at least theta - GRAM_DELTA - SW3_RCP_DELTA - 1e-12,
-// and a lane is expanded only from that threshold minus another
-// SW3_RCP_DELTA + 1e-9 on.
+// the radix selection's bound of the m-th lane value is at most 2^-24 below
+// it, so the threshold is at least theta - 2^-24 - GRAM_DELTA -
+// SW3_RCP_DELTA - 1e-12, and a lane is expanded only from that threshold
+// minus another SW3_RCP_DELTA + 1e-9 on.
 constexpr int SW3_A = 4;              // values of a per wave
 constexpr int SW3_MMAX = 16;          // bounded sweep for m up to this
-constexpr double SW3_TH_SLACK = GRAM_DELTA + 4.0 * SW3_RCP_DELTA + 1e-8;
+// (2^-24: the radix selection's threshold may lie that far below the m-th lane value)
+constexpr double SW3_TH_SLACK = GRAM_DELTA + 4.0 * SW3_RCP_DELTA + 5.9604644775390625e-8 + 1e-8;
 // high word of PIV_TOL: den > PIV_TOL implies hi(den) >= SW3_HI_PIV
 constexpr int SW3_HI_PIV = (int)(__builtin_bit_cast(unsigned long long, PIV_TOL) >> 32);
 

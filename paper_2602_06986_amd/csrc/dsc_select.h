@@ -1,6 +1,8 @@
-// Radix selection of the K-th largest positive double (bits of a positive
-// double are monotone in its value): three 12-bit levels below the sign
-// bit.  Shared by the screening pool and the L0 band.
+// Radix selection of a lower bound of the K-th largest positive value: two
+// 12-bit levels of a fixed-point key.  Its users need only a bound at most
+// the K-th value (the screening pool and the L0 band reach below it by
+// their own margins), and two levels bound it within 2^-24.  Shared by the
+// screening pool and the L0 band.
 #pragma once
 
 #include <algorithm>
@@ -10,9 +12,11 @@
 namespace dsc {
 
 // Key of a score in [0, 1): its 52-bit fixed-point value (monotone, uniform
-// resolution; values >= 1 saturate).  Three 12-bit levels cover bits 51..16,
-// so the selected threshold is exact in double and within 2^-36 of the
-// K-th largest value.
+// resolution; values >= 1 saturate).  The two 12-bit levels cover bits
+// 51..28, so the selected threshold is exact in double, at most the K-th
+// largest value and within 2^-24 of it.
+constexpr int RADIX_LEVELS = 2;
+
 static __device__ __forceinline__ uint64_t fx_key(double x) {
     const double c = x < 0.9999999999999999 ? x : 0.9999999999999999;
     return (uint64_t)(c * 4503599627370496.0);          // * 2^52
@@ -20,8 +24,8 @@ static __device__ __forceinline__ uint64_t fx_key(double x) {
 
 // One radix selection per list: x[0..N) holds the values (entries <= 0 are
 // ignored), K the rank wanted; hist is a 4096-bin scratch histogram, sel
-// the three selected 12-bit digits, st[0] the remaining rank and st[1] the
-// take-all flag (fewer than K positive entries).
+// the selected 12-bit digits (sel[2] stays 0), st[0] the remaining rank and
+// st[1] the take-all flag (fewer than K positive entries).
 struct RadixArgs {
     const double* x;
     int64_t N;
@@ -133,7 +137,7 @@ static inline void radix_select(const RadixArgs* Ad, int nl, int64_t Nmax, hipSt
     const ctab<RadixArgs> A = ct(Ad);
     const unsigned hb = (unsigned)std::min<int64_t>(1024, std::max<int64_t>(1, cdiv(Nmax, 256 * 8)));
     k_radix_init<<<nl, 256, 0, s>>>(A);
-    for (int level = 0; level < 3; level++) {
+    for (int level = 0; level < RADIX_LEVELS; level++) {
         k_hist<<<dim3(hb, nl), 256, 0, s>>>(A, level);
         k_find<<<nl, 256, 0, s>>>(A, level);
     }
