@@ -384,6 +384,14 @@ struct ListItem {
     int32_t kind, op, ca, cb;
 };
 
+__device__ __forceinline__ void d_score_item(const ListItem it, Ops o, const uint8_t* __restrict__ valid,
+                                             int n, int T, int mode, const double* __restrict__ Yc,
+                                             const double* __restrict__ syy, int64_t N,
+                                             double* __restrict__ scores, unsigned* nok,
+                                             uint8_t* __restrict__ r2v, double* __restrict__ r2m,
+                                             double* __restrict__ r2q, int64_t off2, int64_t off3);
+
+// One wave per listed candidate (exact two-pass score).
 __device__ __forceinline__ void d_score_list(const ListItem* __restrict__ items, int64_t m,
                                                     Ops o, const uint8_t* __restrict__ valid,
                                                     int n, int T, int mode,
@@ -393,9 +401,23 @@ __device__ __forceinline__ void d_score_list(const ListItem* __restrict__ items,
                                                     unsigned long long* __restrict__ nscored,
                                                     uint8_t* __restrict__ r2v, double* __restrict__ r2m,
                                                     double* __restrict__ r2q, int64_t off2, int64_t off3) {
+    // the block's valid candidates are counted in LDS and added once
+    __shared__ unsigned nok;
+    if (threadIdx.x == 0) nok = 0u;
+    __syncthreads();
     const int64_t w = (int64_t)blockIdx.x * 4 + wave_id();
-    if (w >= m) return;
-    const ListItem it = items[w];
+    if (w < m) d_score_item(items[w], o, valid, n, T, mode, Yc, syy, N, scores, &nok, r2v, r2m, r2q,
+                            off2, off3);
+    __syncthreads();
+    if (threadIdx.x == 0 && nok) atomicAdd(nscored, (unsigned long long)nok);
+}
+
+__device__ __forceinline__ void d_score_item(const ListItem it, Ops o, const uint8_t* __restrict__ valid,
+                                             int n, int T, int mode, const double* __restrict__ Yc,
+                                             const double* __restrict__ syy, int64_t N,
+                                             double* __restrict__ scores, unsigned* nok,
+                                             uint8_t* __restrict__ r2v, double* __restrict__ r2m,
+                                             double* __restrict__ r2q, int64_t off2, int64_t off3) {
     Cand c{it.kind, it.op, it.ca, it.cb, OP_NONE, -1, -1};
     bool ok = valid[c.ca] && (c.kind < 2 || valid[c.cb]);
     if (c.kind == 0) ok = valid[c.ca];
@@ -406,7 +428,7 @@ __device__ __forceinline__ void d_score_list(const ListItem* __restrict__ items,
             for (int t = 0; t < (mode ? 1 : T); t++) scores[(int64_t)t * N + it.id] = __longlong_as_double(-1LL);
             return;
         }
-        atomicAdd(nscored, 1ull);
+        atomicAdd(nok, 1u);
         if (r2v && it.id >= off2 && it.id < off3) {
             r2v[it.id - off2] = 1;
             r2m[it.id - off2] = mean;
@@ -1580,6 +1602,7 @@ __device__ __forceinline__ void d_fixup(const int64_t* __restrict__ ids,
                                                uint8_t* __restrict__ r2v, double* __restrict__ r2m,
                                                double* __restrict__ r2q) {
     const int64_t m = min((int64_t)*cnt, cap);
+    unsigned nfix = 0;                                  // counted per wave, added once
     for (int64_t w = (int64_t)blockIdx.x * 4 + wave_id(); w < m; w += (int64_t)gridDim.x * 4) {
         const int64_t id = ids[w];
         Cand c;
@@ -1587,7 +1610,7 @@ __device__ __forceinline__ void d_fixup(const int64_t* __restrict__ ids,
         double r[TMAX], mean = 0.0, msq = 0.0;
         ok = ok && wave_exact_r<TMAX>(c, o, n, T, Yc, syy, r, &mean, &msq);
         if ((threadIdx.x & 63) != 0 || !ok) continue;
-        atomicAdd(nscored, 1ull);
+        nfix++;
         if (r2v && id >= ev.sd.off[2] && id < ev.sd.off[3]) {     // rung-2 operand statistics
             r2v[id - ev.sd.off[2]] = 1;
             r2m[id - ev.sd.off[2]] = mean;
@@ -1601,9 +1624,9 @@ __device__ __forceinline__ void d_fixup(const int64_t* __restrict__ ids,
             for (int t = 0; t < T; t++) scores[(int64_t)t * N + id] = fabs(r[t]);
         }
     }
+    if ((threadIdx.x & 63) == 0 && nfix) atomicAdd(nscored, (unsigned long long)nfix);
 }
 
-// Rank sort of the pool by (-score, ID).
 // Sort of the pool by (-score, ID) as ranks: entry i's sorted position is
 // the number of entries before it.  Blocks take a tile of 256 entries i and
 // a chunk of RCH entries j staged in LDS (grid-strided over both, so any
