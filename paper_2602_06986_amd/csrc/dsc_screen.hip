@@ -323,6 +323,19 @@ __device__ __forceinline__ bool cand_of_id(const EvalCtx& e, int64_t id, Cand& c
     return c.ca >= 0 && c.cb >= 0 && e.valid[c.ca] && e.valid[c.cb];
 }
 
+// One slot of a counter-indexed list for every active lane of the wave
+// (lane order), with a single atomic: for appends made inside divergent
+// code, where the active lanes are exactly those that append.
+__device__ __forceinline__ unsigned long long wave_slot(unsigned long long* ctr) {
+    const uint64_t m = __builtin_amdgcn_ballot_w64(true);
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((long long)m) - 1;
+    unsigned long long base = 0;
+    if (lane == leader) base = atomicAdd(ctr, (unsigned long long)__popcll(m));
+    base = __shfl(base, leader, 64);
+    return base + (unsigned long long)__popcll(m & ((1ull << lane) - 1ull));
+}
+
 // Exact two-pass Pearson of one candidate against T centered targets by one
 // wave.  Returns false when the candidate is not finite or is constant.
 template <int TMAX>
@@ -659,7 +672,7 @@ __global__ __launch_bounds__(64 * pair_split<LIST>()) void k_screen_pairs(ctab<P
             }
             if (!(kappa <= KAPPA_MAX)) {
                 // the shift was far from the mean: decide exactly in the fix-up pass
-                const unsigned long long slot = atomicAdd(g.fix_cnt, 1ull);
+                const unsigned long long slot = wave_slot(g.fix_cnt);
                 if ((int64_t)slot < g.fix_cap) {
                     g.fix_ids[slot] = id;
                     for (int t = 0; t < (g.mode ? 1 : g.T); t++) g.scores[(int64_t)t * g.N + id] = nanv;
@@ -952,7 +965,7 @@ __global__ __launch_bounds__(256) void k_screen_r3(R3Args g) {
                     if (ff <= 1e-12 * nn * (g.msq[i] + q2)) kappa = INFINITY;
                 }
                 if (!(kappa <= KAPPA_MAX)) {
-                    const unsigned long long slot = atomicAdd(g.fix_cnt, 1ull);
+                    const unsigned long long slot = wave_slot(g.fix_cnt);
                     if ((int64_t)slot < g.fix_cap) {
                         g.fix_ids[slot] = id;
                         for (int t = 0; t < (g.mode ? 1 : g.T); t++) g.scores[(int64_t)t * g.N + id] = nanv;
@@ -1248,7 +1261,7 @@ __global__ __launch_bounds__(256) void k_screen_lp(PairArgs g, const void* __res
         const bool ok = flag == 1.0;
         if (flag == 2.0) {
             if (kb == 0) {
-                const unsigned long long slot = atomicAdd(g.fix_cnt, 1ull);
+                const unsigned long long slot = wave_slot(g.fix_cnt);
                 if ((int64_t)slot < g.fix_cap) g.fix_ids[slot] = id;
                 if (g.mode == DISCOVER_SCORE_MAX) g.scores[id] = nanv;
             }
@@ -1478,7 +1491,7 @@ __global__ __launch_bounds__(256) void k_screen_lp1(PairArgs g, const void* __re
         const double nanv = __longlong_as_double(-1LL);
         if (state == 3.0) {
             if (kb == 0) {
-                const unsigned long long slot = atomicAdd(g.fix_cnt, 1ull);
+                const unsigned long long slot = wave_slot(g.fix_cnt);
                 if ((int64_t)slot < g.fix_cap) g.fix_ids[slot] = id;
                 if (g.mode == DISCOVER_SCORE_MAX) g.scores[id] = nanv;
             }
