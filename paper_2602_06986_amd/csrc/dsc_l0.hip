@@ -26,11 +26,14 @@ constexpr double SW3_RCP_DELTA = 4.76837158203125e-7;  // 2^-21: D = 3 sweep val
 constexpr double TAU_TIE = 1e-11;     // RSS tie tolerance relative to ||y - mean||^2
 
 // ------------------------------------------------------------------ prep
-// One wave per row (rows 0..S-1 of F, row S = y): Z = (f - mean) / ||f - mean||.
+// One wave per row (rows 0..S-1 of F, row S = y): Z = (f - mean) / ||f - mean||,
+// and when nrm is given, nrm[row] = |Z row|^2 for the rows of F (0 for a
+// constant row).
 __device__ __forceinline__ void d_l0_prep(int n, int S, const double* __restrict__ F,
                                                  int64_t ldf, const double* __restrict__ y,
                                                  int ldz, double* __restrict__ Z,
-                                                 double* __restrict__ yy) {
+                                                 double* __restrict__ yy,
+                                                 double* __restrict__ nrm = nullptr) {
     const int row = blockIdx.x * 4 + wave_id();
     const int lane = threadIdx.x & 63;
     if (row > S) return;
@@ -46,85 +49,114 @@ __device__ __forceinline__ void d_l0_prep(int n, int S, const double* __restrict
     q = wave_sum(q);
     const double inv = q > 0.0 ? 1.0 / sqrt(q) : 0.0;
     double* z = Z + (int64_t)row * ldz;
-    for (int i = lane; i < ldz; i += 64) z[i] = i < n ? (f[i] - m) * inv : 0.0;
+    double zz = 0.0;
+    for (int i = lane; i < ldz; i += 64) {
+        const double zi = i < n ? (f[i] - m) * inv : 0.0;
+        z[i] = zi;
+        zz += zi * zi;
+    }
+    if (nrm && row < S) {
+        zz = wave_sum(zz);
+        if (lane == 0) nrm[row] = zz;
+    }
     if (row == S && lane == 0) *yy = q;
 }
 
 // G = Z Z^T for M = S + 1 rows on the FP64 matrix cores.  A block covers a
-// 64 x 64 tile of the upper triangle (mirrored when written), each wave a
-// 32 x 32 quarter as 2 x 2 products of v_mfma_f64_16x16x4f64.  That
-// instruction takes A[i][k] from lane i + 16 k and B[k][j] from lane j + 16 k
-// and leaves D[i][j] in lane j + 16 (i mod 4), register i / 4.  The sum over
-// samples may run in any order, so lane l takes samples k0 + 4 (l / 16) +
-// s at step s of a chunk of 16: its four samples of a row are one 32-byte
-// load, and the four lanes of a row read 128 contiguous bytes.  The next
-// chunk's fragments are loaded while the current chunk's 16 products run.
-// ldz is a multiple of 16 and Z is zero past n, rows are 32-byte aligned.
+// 32 x 32 tile of the upper triangle (mirrored when written) as 2 x 2
+// products of v_mfma_f64_16x16x4f64, and its four waves split the sum over
+// samples into four runs of whole 16-sample chunks; the partial tiles meet
+// in LDS and are added in wave order, so the result does not depend on
+// timing.  (Each wave owning a whole chain keeps the MFMA pipe busy between
+// loads; a 64 x 64 tile per block left small Gram matrices to a few dozen
+// blocks, each waiting on its loads.)  The instruction takes A[i][k] from
+// lane i + 16 k and B[k][j] from lane j + 16 k and leaves D[i][j] in lane
+// j + 16 (i mod 4), register i / 4.  The sum over samples may run in any
+// order, so lane l takes samples k0 + 4 (l / 16) + s at step s of a chunk
+// of 16: its four samples of a row are one 32-byte load, and the four lanes
+// of a row read 128 contiguous bytes.  The next chunk's fragments are
+// loaded while the current chunk's 16 products run.  ldz is a multiple of
+// 16 and Z is zero past n, rows are 32-byte aligned.
 typedef double dsc_v4d __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ void d_gram(int M, int ldz, int nk, const double* __restrict__ Z,
                                        double* __restrict__ G, int ldg) {
-    const int bi = blockIdx.y * 64, bj = blockIdx.x * 64;
-    if (bj < bi) return;                      // lower triangle mirrored below
+    const int bi = blockIdx.y * 32, bj = blockIdx.x * 32;
+    if (bj < bi) return;                      // lower triangle mirrored below (block-uniform)
+    __shared__ dsc_v4d part[3][4][64];        // waves 1..3: their 2 x 2 partial tiles
     const int wv = wave_id();
     const int lane = threadIdx.x & 63;
-    const int wi = bi + 32 * (wv >> 1), wj = bj + 32 * (wv & 1);
-    if (wj + 31 < wi) return;                 // a wave wholly below the diagonal
     const int r16 = lane & 15, kg = 4 * (lane >> 4);
-    const double* pa[2];
-    const double* pb[2];
-#pragma unroll
-    for (int t = 0; t < 2; t++) {
-        pa[t] = Z + (int64_t)min(wi + 16 * t + r16, M - 1) * ldz + kg;
-        pb[t] = Z + (int64_t)min(wj + 16 * t + r16, M - 1) * ldz + kg;
-    }
+    const int nch = nk >> 4;                  // chunks of 16 samples; wave wv takes [ch0, ch1)
+    const int ch0 = (nch * wv) >> 2, ch1 = (nch * (wv + 1)) >> 2;
     dsc_v4d acc[2][2];
 #pragma unroll
     for (int u = 0; u < 2; u++)
 #pragma unroll
         for (int v = 0; v < 2; v++) acc[u][v] = dsc_v4d{0.0, 0.0, 0.0, 0.0};
-    double4 A[2], B[2];
-#pragma unroll
-    for (int t = 0; t < 2; t++) { A[t] = *(const double4*)pa[t]; B[t] = *(const double4*)pb[t]; }
-    for (int k0 = 0; k0 < nk; k0 += 16) {
-        double4 An[2], Bn[2];
-        const int kn = min(k0 + 16, nk - 16);     // the last chunk reloads itself
+    if (ch1 > ch0) {                          // (wave-uniform)
+        const double* pa[2];
+        const double* pb[2];
 #pragma unroll
         for (int t = 0; t < 2; t++) {
-            An[t] = *(const double4*)(pa[t] + kn);
-            Bn[t] = *(const double4*)(pb[t] + kn);
+            pa[t] = Z + (int64_t)min(bi + 16 * t + r16, M - 1) * ldz + kg;
+            pb[t] = Z + (int64_t)min(bj + 16 * t + r16, M - 1) * ldz + kg;
         }
+        double4 A[2], B[2];
+        const int kbeg = ch0 * 16, klast = ch1 * 16 - 16;
+#pragma unroll
+        for (int t = 0; t < 2; t++) { A[t] = *(const double4*)(pa[t] + kbeg); B[t] = *(const double4*)(pb[t] + kbeg); }
+        for (int k0 = kbeg; k0 <= klast; k0 += 16) {
+            double4 An[2], Bn[2];
+            const int kn = min(k0 + 16, klast);   // the last chunk reloads itself
+#pragma unroll
+            for (int t = 0; t < 2; t++) {
+                An[t] = *(const double4*)(pa[t] + kn);
+                Bn[t] = *(const double4*)(pb[t] + kn);
+            }
+#pragma unroll
+            for (int u = 0; u < 2; u++)
+#pragma unroll
+                for (int v = 0; v < 2; v++) {
+                    acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[u].x, B[v].x, acc[u][v], 0, 0, 0);
+                    acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[u].y, B[v].y, acc[u][v], 0, 0, 0);
+                    acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[u].z, B[v].z, acc[u][v], 0, 0, 0);
+                    acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[u].w, B[v].w, acc[u][v], 0, 0, 0);
+                }
+            // the loaded fragments pass through an empty asm: without it the
+            // compiler folds this load into a load at the top of the next
+            // chunk that waits for its own result
+#pragma unroll
+            for (int t = 0; t < 2; t++) {
+                asm("" : "+v"(An[t].x), "+v"(An[t].y), "+v"(An[t].z), "+v"(An[t].w));
+                asm("" : "+v"(Bn[t].x), "+v"(Bn[t].y), "+v"(Bn[t].z), "+v"(Bn[t].w));
+                A[t] = An[t]; B[t] = Bn[t];
+            }
+        }
+    }
+    if (wv > 0)
 #pragma unroll
         for (int u = 0; u < 2; u++)
 #pragma unroll
-            for (int v = 0; v < 2; v++) {
-                acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[u].x, B[v].x, acc[u][v], 0, 0, 0);
-                acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[u].y, B[v].y, acc[u][v], 0, 0, 0);
-                acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[u].z, B[v].z, acc[u][v], 0, 0, 0);
-                acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[u].w, B[v].w, acc[u][v], 0, 0, 0);
-            }
-        // the loaded fragments pass through an empty asm: without it the
-        // compiler folds this load into a load at the top of the next chunk
-        // that waits for its own result
-#pragma unroll
-        for (int t = 0; t < 2; t++) {
-            asm("" : "+v"(An[t].x), "+v"(An[t].y), "+v"(An[t].z), "+v"(An[t].w));
-            asm("" : "+v"(Bn[t].x), "+v"(Bn[t].y), "+v"(Bn[t].z), "+v"(Bn[t].w));
-            A[t] = An[t]; B[t] = Bn[t];
-        }
-    }
+            for (int v = 0; v < 2; v++) part[wv - 1][2 * u + v][lane] = acc[u][v];
+    __syncthreads();
+    if (wv != 0) return;
 #pragma unroll
     for (int u = 0; u < 2; u++)
 #pragma unroll
-        for (int v = 0; v < 2; v++)
+        for (int v = 0; v < 2; v++) {
+            dsc_v4d t = acc[u][v];
+#pragma unroll
+            for (int w = 0; w < 3; w++) t += part[w][2 * u + v][lane];
 #pragma unroll
             for (int r = 0; r < 4; r++) {
-                const int i = wi + 16 * u + (lane >> 4) + 4 * r, j = wj + 16 * v + r16;
+                const int i = bi + 16 * u + (lane >> 4) + 4 * r, j = bj + 16 * v + r16;
                 if (i < M && j < M && i <= j) {
-                    G[(int64_t)i * ldg + j] = acc[u][v][r];
-                    G[(int64_t)j * ldg + i] = acc[u][v][r];
+                    G[(int64_t)i * ldg + j] = t[r];
+                    G[(int64_t)j * ldg + i] = t[r];
                 }
             }
+        }
 }
 
 // ----------------------------------------------------------------- sweep
@@ -750,13 +782,13 @@ __device__ __forceinline__ void d_rank_models(const int4* __restrict__ band, con
     }
 }
 
-// Residuals of the chosen models: one block per model.
-__device__ __forceinline__ void d_resid(int n, int D, const double* __restrict__ F,
+// Residual of chosen model q (NaN for a missing model), by the 256 threads
+// of a block.
+__device__ __forceinline__ void d_resid(int q, int n, int D, const double* __restrict__ F,
                                                int64_t ldf, const double* __restrict__ y,
                                                const int32_t* __restrict__ sub,
                                                const double* __restrict__ coef,
                                                double* __restrict__ out, int64_t ldr, int sub_ld, int coef_ld) {
-    const int q = blockIdx.x;
     const int32_t* s = sub + q * sub_ld;
     const double* c = coef + q * coef_ld;
     for (int i = threadIdx.x; i < n; i += 256) {
@@ -790,11 +822,28 @@ __global__ __launch_bounds__(256) void k_l0_prep(ctab<PrepArgs> A) {
     d_l0_prep(a.n, a.S, a.F, a.ldf, a.y, a.ldz, a.Z, a.yy);
 }
 
-// One problem (used by OMP): grid (row blocks of 4).
-__global__ __launch_bounds__(256) void k_l0_prep_one(int n, int S, const double* __restrict__ F,
-                                                     int64_t ldf, const double* __restrict__ y, int ldz,
-                                                     double* __restrict__ Z, double* __restrict__ yy) {
-    d_l0_prep(n, S, F, ldf, y, ldz, Z, yy);
+// OMP set-up for one problem: grid (row blocks of 4).  Standardised rows,
+// their squared norms, and (block 0) the starting active set.
+// Warm start: the rows of init that lie in 0..S-1, first occurrences only,
+// in order; a missing or repeated row leaves the model one row shorter.
+__global__ __launch_bounds__(256) void k_omp_prep(int n, int S, const double* __restrict__ F,
+                                                  int64_t ldf, const double* __restrict__ y, int ldz,
+                                                  double* __restrict__ Z, double* __restrict__ yy,
+                                                  double* __restrict__ nrm,
+                                                  int32_t* __restrict__ active, int D_max,
+                                                  const int32_t* __restrict__ init, int n_init,
+                                                  int32_t* __restrict__ nact) {
+    d_l0_prep(n, S, F, ldf, y, ldz, Z, yy, nrm);
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    int c = 0;
+    for (int q = 0; q < n_init; q++) {
+        const int r = init[q];
+        bool keep = r >= 0 && r < S;
+        for (int t = 0; t < c; t++) keep = keep && active[t] != r;
+        if (keep) active[c++] = r;
+    }
+    for (int q = c; q < D_max; q++) active[q] = -1;
+    *nact = c;
 }
 
 // grid (column tiles, row tiles, problems)
@@ -802,7 +851,7 @@ __global__ __launch_bounds__(256) void k_gram(ctab<PrepArgs> A) {
     const PrepArgs& a = tab(A, blockIdx.z);
     DSC_GLOBAL(a.Z); DSC_GLOBAL(a.G);
     const int M = a.S + 1;
-    if ((int)blockIdx.x * 64 >= M || (int)blockIdx.y * 64 >= M) return;
+    if ((int)blockIdx.x * 32 >= M || (int)blockIdx.y * 32 >= M) return;
     d_gram(M, a.ldz, a.ldz, a.Z, a.G, a.ldg);
 }
 
@@ -898,19 +947,18 @@ __global__ __launch_bounds__(256) void k_refit_all(ctab<RefitArgs> A, int na,
     }
 }
 
-// grid (problems), 64 threads
-__global__ void k_rank_models(ctab<RefitArgs> A) {
+// grid (problems): the m best models of each problem's band (one thread),
+// then their residuals when asked for (the whole block).
+__global__ __launch_bounds__(256) void k_rank_models(ctab<RefitArgs> A) {
     const RefitArgs& a = tab(A, blockIdx.x);
-    DSC_GLOBAL(a.F); DSC_GLOBAL(a.y); DSC_GLOBAL(a.band); DSC_GLOBAL(a.bcnt); DSC_GLOBAL(a.scratch); DSC_GLOBAL(a.brss); DSC_GLOBAL(a.bcoef); DSC_GLOBAL(a.ids); DSC_GLOBAL(a.yy); DSC_GLOBAL(a.taken); DSC_GLOBAL(a.out_sub); DSC_GLOBAL(a.out_rmse); DSC_GLOBAL(a.out_coef); DSC_GLOBAL(a.chosen);
+    DSC_GLOBAL(a.F); DSC_GLOBAL(a.y); DSC_GLOBAL(a.band); DSC_GLOBAL(a.bcnt); DSC_GLOBAL(a.scratch); DSC_GLOBAL(a.brss); DSC_GLOBAL(a.bcoef); DSC_GLOBAL(a.ids); DSC_GLOBAL(a.yy); DSC_GLOBAL(a.taken); DSC_GLOBAL(a.out_sub); DSC_GLOBAL(a.out_rmse); DSC_GLOBAL(a.out_coef); DSC_GLOBAL(a.chosen); DSC_GLOBAL(a.out_resid);
     d_rank_models(a.band, a.brss, a.bcoef, a.bcnt, a.bcap, a.D, a.m, a.ids, a.yy, a.n, a.taken,
                   a.out_sub, a.out_rmse, a.out_coef, a.chosen, a.sub_ld, a.coef_ld);
-}
-
-// grid (models, problems)
-__global__ __launch_bounds__(256) void k_resid(ctab<RefitArgs> A) {
-    const RefitArgs& a = tab(A, blockIdx.y);
-    DSC_GLOBAL(a.F); DSC_GLOBAL(a.y); DSC_GLOBAL(a.out_sub); DSC_GLOBAL(a.out_coef); DSC_GLOBAL(a.out_resid);
-    d_resid(a.n, a.D, a.F, a.ldf, a.y, a.out_sub, a.out_coef, a.out_resid, a.ldr, a.sub_ld, a.coef_ld);
+    if (!a.out_resid) return;
+    __syncthreads();                             // the chosen models are written
+    for (int q = 0; q < a.m; q++)
+        d_resid(q, a.n, a.D, a.F, a.ldf, a.y, a.out_sub, a.out_coef, a.out_resid, a.ldr, a.sub_ld,
+                a.coef_ld);
 }
 
 // ------------------------------------------------------------------ OMP
@@ -935,97 +983,73 @@ __global__ __launch_bounds__(256) void k_omp_corr(int n, int S, const double* __
     }
 }
 
-// argmax of g by (-g, ID), appended to the active list (single block).
-__global__ __launch_bounds__(256) void k_omp_pick(int S, const double* __restrict__ g,
-                                                  const int64_t* __restrict__ ids,
-                                                  const double* __restrict__ rownorm,
-                                                  int32_t* __restrict__ active,
-                                                  int32_t* __restrict__ nact) {
-    __shared__ double bg[256];
-    __shared__ int bj[256];
-    double best = -2.0;
-    int bi = -1;
-    for (int j = threadIdx.x; j < S; j += 256) {
-        if (!(rownorm[j] > 0.0)) continue;
-        const double v = g[j];
-        if (v > best || (v == best && bi >= 0 && ids[j] < ids[bi])) {
-            best = v;
-            bi = j;
-        }
-    }
-    bg[threadIdx.x] = best;
-    bj[threadIdx.x] = bi;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) {
-            const double v = bg[threadIdx.x + o];
-            const int j = bj[threadIdx.x + o];
-            const int cj = bj[threadIdx.x];
-            if (j >= 0 && (cj < 0 || v > bg[threadIdx.x] || (v == bg[threadIdx.x] && ids[j] < ids[cj]))) {
-                bg[threadIdx.x] = v;
-                bj[threadIdx.x] = j;
-            }
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0 && bj[0] >= 0 && bg[0] >= 0.0) {
-        active[*nact] = bj[0];
-        *nact += 1;
-    }
-}
-
+// One OMP step in one workgroup.  With g given, first the argmax of g by
+// (-g, ID) over the non-constant rows is appended to the active list (none
+// when every row is taken); then the least-squares fit on the active rows,
+// its residual r and, with out_rmse given, sqrt(RSS / n).
 __global__ __launch_bounds__(256) void k_omp_fit(int n, const double* __restrict__ F, int64_t ldf,
                                                  const double* __restrict__ y,
-                                                 const int32_t* __restrict__ active,
-                                                 const int32_t* __restrict__ nact,
+                                                 int32_t* __restrict__ active,
+                                                 int32_t* __restrict__ nact,
                                                  double* __restrict__ A, double* __restrict__ coef,
                                                  double* __restrict__ rss, double* __restrict__ r,
-                                                 int use_lds) {
+                                                 int use_lds, int S, const double* __restrict__ g,
+                                                 const int64_t* __restrict__ ids,
+                                                 const double* __restrict__ rownorm,
+                                                 double* __restrict__ out_rmse) {
     __shared__ int idx[DISCOVER_MAX_D];
     __shared__ double cf[DISCOVER_MAX_D + 1];
     __shared__ double rs;
+    __shared__ double bg[256];
+    __shared__ int bj[256];
+    __shared__ int s_d;
     extern __shared__ double dsm[];              // (D_max + 2) * n doubles when use_lds
-    const int d = *nact;
-    if (threadIdx.x < d) idx[threadIdx.x] = active[threadIdx.x];
+    if (threadIdx.x == 0) s_d = *nact;
+    __syncthreads();
+    const int d0 = s_d;
+    int pick = -1;
+    if (g) {
+        double best = -2.0;
+        int bi = -1;
+        for (int j = threadIdx.x; j < S; j += 256) {
+            if (!(rownorm[j] > 0.0)) continue;
+            const double v = g[j];
+            if (v > best || (v == best && bi >= 0 && ids[j] < ids[bi])) {
+                best = v;
+                bi = j;
+            }
+        }
+        bg[threadIdx.x] = best;
+        bj[threadIdx.x] = bi;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if (threadIdx.x < o) {
+                const double v = bg[threadIdx.x + o];
+                const int j = bj[threadIdx.x + o];
+                const int cj = bj[threadIdx.x];
+                if (j >= 0 && (cj < 0 || v > bg[threadIdx.x] || (v == bg[threadIdx.x] && ids[j] < ids[cj]))) {
+                    bg[threadIdx.x] = v;
+                    bj[threadIdx.x] = j;
+                }
+            }
+            __syncthreads();
+        }
+        pick = bj[0] >= 0 && bg[0] >= 0.0 ? bj[0] : -1;
+        if (threadIdx.x == 0 && pick >= 0) {
+            active[d0] = pick;
+            *nact = d0 + 1;
+        }
+    }
+    const int d = pick >= 0 ? d0 + 1 : d0;
+    if (threadIdx.x < d) idx[threadIdx.x] = threadIdx.x < d0 ? active[threadIdx.x] : pick;
     __syncthreads();
     if (use_lds) block_lsq(n, d, idx, F, ldf, y, dsm, cf, &rs, r);
     else block_lsq(n, d, idx, F, ldf, y, A, cf, &rs, r);
     if (threadIdx.x == 0) {
         for (int j = 0; j <= d; j++) coef[j] = cf[j];
         *rss = rs;
+        if (out_rmse) *out_rmse = sqrt(rs / n);
     }
-}
-
-__global__ __launch_bounds__(256) void k_row_norm(int S, int ldz, const double* __restrict__ Z, int n,
-                                                  double* __restrict__ nrm) {
-    const int j = blockIdx.x * 4 + wave_id();
-    const int lane = threadIdx.x & 63;
-    if (j >= S) return;
-    double s = 0.0;
-    for (int i = lane; i < n; i += 64) s += Z[(int64_t)j * ldz + i] * Z[(int64_t)j * ldz + i];
-    s = wave_sum(s);
-    if (lane == 0) nrm[j] = s;
-}
-
-// OMP set-up and result, as kernels so that no host copy is needed.
-// Warm start: the rows of init that lie in 0..S-1, first occurrences only,
-// in order; a missing or repeated row leaves the model one row shorter.
-__global__ void k_omp_init(int32_t* __restrict__ active, int D_max, const int32_t* __restrict__ init,
-                           int n_init, int S, int32_t* __restrict__ nact) {
-    if (threadIdx.x != 0) return;
-    int c = 0;
-    for (int q = 0; q < n_init; q++) {
-        const int r = init[q];
-        bool keep = r >= 0 && r < S;
-        for (int t = 0; t < c; t++) keep = keep && active[t] != r;
-        if (keep) active[c++] = r;
-    }
-    for (int q = c; q < D_max; q++) active[q] = -1;
-    *nact = c;
-}
-
-__global__ void k_omp_rmse(const double* __restrict__ rss, int n, double* __restrict__ out) {
-    if (threadIdx.x == 0) *out = sqrt(*rss / n);
 }
 
 // ================================================================== host
@@ -1182,7 +1206,7 @@ void l0_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D
     {
         KTimer kt(ctx, st, "l0_gram");
         k_l0_prep<<<dim3((unsigned)cdiv(Smax + 1, 4), nb), 256, 0, st>>>(dpa);
-        const unsigned gt = (unsigned)cdiv(Smax + 1, 64);
+        const unsigned gt = (unsigned)cdiv(Smax + 1, 32);
         k_gram<<<dim3(gt, gt, nb), 256, 0, st>>>(dpa);
         check_launch("k_gram");
     }
@@ -1298,7 +1322,8 @@ void l0_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D
             g.lidx = sa[b].lidx; g.lval = sa[b].lval; g.lcnt = sa[b].lcnt;
             ra[q] = RadixArgs{g.lidx ? g.lval : g.lane_q, g.n_lanes, m, (uint32_t*)(bb + v[7]),
                               (uint32_t*)(misc + 32), (int64_t*)(misc + 16), g.lidx ? g.lcnt : nullptr};
-            fills.push_back(fill_seg(misc, 16, 0u));
+            fills.push_back(fill_seg(misc, 48, 0u));              // bcnt, pcnt, st, sel
+            fills.push_back(fill_seg(bb + v[7], 4096 * 4, 0u));   // radix histogram
             lanes_max = std::max(lanes_max, g.n_lanes);
             RefitArgs& f = fa[q];
             f = RefitArgs{};
@@ -1334,12 +1359,8 @@ void l0_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D
                                                                                    sld, rl);
             check_launch("k_refit");
         }
-        k_rank_models<<<na, 64, 0, st>>>(dfa);
+        k_rank_models<<<na, 256, 0, st>>>(dfa);
         check_launch("k_rank_models");
-        if (outs[0].resid) {
-            k_resid<<<dim3(m, na), 256, 0, st>>>(dfa);
-            check_launch("k_resid");
-        }
         if (ctx->capturing) {                   // capacities are checked after the replay
             if (checks)
                 for (int q = 0; q < na; q++) checks->push_back(BandCheck{ba[q].bcnt, cap[act[q]]});
@@ -1443,24 +1464,22 @@ void omp_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int 
         double* rss = ctx->buf<double>("omprss" + sfx, 1);
         double* coef = out_coef + (int64_t)b * (D_max + 1);
         KTimer kt(ctx, st, "omp");
-        k_l0_prep_one<<<(unsigned)cdiv(pb.S + 1, 4), 256, 0, st>>>(pb.n, pb.S, pb.F, pb.ldf, pb.y,
-                                                                   ldz, Z, yy);
-        k_row_norm<<<(unsigned)cdiv(pb.S, 4), 256, 0, st>>>(pb.S, ldz, Z, pb.n, nrm);
-        k_omp_init<<<1, 64, 0, st>>>(active, D_max, n_init ? init_active + (int64_t)b * init_ld : nullptr,
-                                     n_init, pb.S, nact);
+        k_omp_prep<<<(unsigned)cdiv(pb.S + 1, 4), 256, 0, st>>>(
+            pb.n, pb.S, pb.F, pb.ldf, pb.y, ldz, Z, yy, nrm, active, D_max,
+            n_init ? init_active + (int64_t)b * init_ld : nullptr, n_init, nact);
         // the QR's columns in LDS when they fit in 64 KB
         const size_t qr_bytes = (size_t)(D_max + 2) * pb.n * sizeof(double);
         const int qr_lds = qr_bytes <= 65536 ? 1 : 0;
         const size_t dyn = qr_lds ? qr_bytes : 0;
-        k_omp_fit<<<1, 256, dyn, st>>>(pb.n, pb.F, pb.ldf, pb.y, active, nact, A, coef, rss, r, qr_lds);
+        k_omp_fit<<<1, 256, dyn, st>>>(pb.n, pb.F, pb.ldf, pb.y, active, nact, A, coef, rss, r, qr_lds,
+                                       pb.S, nullptr, pb.ids, nrm, n_init < D_max ? nullptr : out_rmse + b);
         for (int step = n_init; step < D_max; step++) {
             k_omp_corr<<<(unsigned)cdiv(pb.S, 4), 256, 0, st>>>(pb.n, pb.S, Z, ldz, r, active,
                                                                 nact, g);
-            k_omp_pick<<<1, 256, 0, st>>>(pb.S, g, pb.ids, nrm, active, nact);
             k_omp_fit<<<1, 256, dyn, st>>>(pb.n, pb.F, pb.ldf, pb.y, active, nact, A, coef, rss, r,
-                                           qr_lds);
+                                           qr_lds, pb.S, g, pb.ids, nrm,
+                                           step + 1 == D_max ? out_rmse + b : nullptr);
         }
-        k_omp_rmse<<<1, 64, 0, st>>>(rss, pb.n, out_rmse + b);
         check_launch("omp");
     }
     if (!ctx->capturing) {

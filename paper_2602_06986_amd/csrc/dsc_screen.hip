@@ -3013,7 +3013,8 @@ static void select_round(discover_ctx* ctx, const discover_problem* probs,
         a.out_ids = outs[L.b].ids + (int64_t)L.t * k;
         a.out_sc = outs[L.b].sc + (int64_t)L.t * k;
         ra[q] = RadixArgs{a.sc, P.N, L.K, hist, sel, stv, nullptr};
-        fills.push_back(fill_seg(misc, 16, 0u));            // pool count, maximum error
+        fills.push_back(fill_seg(misc, 48, 0u));            // pool count, maximum error, st, sel
+        fills.push_back(fill_seg(hist, 4096 * 4, 0u));
         Nmax = std::max(Nmax, P.N);
         capmax = std::max(capmax, L.cap);
         Kmax = std::max(Kmax, L.K);

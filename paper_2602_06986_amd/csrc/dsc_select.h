@@ -25,7 +25,9 @@ static __device__ __forceinline__ uint64_t fx_key(double x) {
 // One radix selection per list: x[0..N) holds the values (entries <= 0 are
 // ignored), K the rank wanted; hist is a 4096-bin scratch histogram, sel
 // the selected 12-bit digits (sel[2] stays 0), st[0] the remaining rank and
-// st[1] the take-all flag (fewer than K positive entries).
+// st[1] the take-all flag (fewer than K positive entries).  Before the
+// selection, hist, st and sel must be zero (the callers clear them with
+// their other counters, which saves a launch).
 struct RadixArgs {
     const double* x;
     int64_t N;
@@ -35,17 +37,6 @@ struct RadixArgs {
     int64_t* st;
     const unsigned long long* Nd;   // or NULL: device count of entries (at most N)
 };
-
-static __global__ __launch_bounds__(256) void k_radix_init(ctab<RadixArgs> A) {
-    const RadixArgs& a = tab(A, blockIdx.x);
-    DSC_GLOBAL(a.hist); DSC_GLOBAL(a.sel); DSC_GLOBAL(a.st);
-    for (int b = threadIdx.x; b < 4096; b += 256) a.hist[b] = 0;
-    if (threadIdx.x < 4) a.sel[threadIdx.x] = 0;
-    if (threadIdx.x == 0) {
-        a.st[0] = a.K;
-        a.st[1] = 0;
-    }
-}
 
 // grid (blocks, lists)
 static __global__ __launch_bounds__(256) void k_hist(ctab<RadixArgs> A, int level) {
@@ -74,7 +65,8 @@ static __global__ __launch_bounds__(256) void k_hist(ctab<RadixArgs> A, int leve
 
 // One block of 256 threads per list: thread t owns bins [16t, 16t+16); a
 // suffix scan over threads gives the count above each range.  The
-// histogram is cleared for the next level after it has been read.
+// histogram is cleared for the next level after it has been read.  Level 0
+// starts from rank K, later levels from the rank left in st[0].
 static __global__ __launch_bounds__(256) void k_find(ctab<RadixArgs> A, int level) {
     const RadixArgs& a = tab(A, blockIdx.x);
     DSC_GLOBAL(a.hist); DSC_GLOBAL(a.sel); DSC_GLOBAL(a.st);
@@ -99,9 +91,9 @@ static __global__ __launch_bounds__(256) void k_find(ctab<RadixArgs> A, int leve
         part[t] += v;
         __syncthreads();
     }
-    const int64_t K = st[0];
+    const int64_t K = level == 0 ? a.K : st[0];
     const int64_t total = part[0];
-    const bool all = st[1] != 0 || total < K;
+    const bool all = (level > 0 && st[1] != 0) || total < K;
     __syncthreads();
     if (all) {
         if (t == 0) {
@@ -130,13 +122,13 @@ static __device__ __forceinline__ double select_threshold(const uint32_t* sel, c
     return (double)key * 2.220446049250313e-16;          // * 2^-52 (exact)
 }
 
-// Launch the selections of nl lists (device table A); afterwards each
-// list's sel/st describe its K-th largest positive entry.
+// Launch the selections of nl lists (device table A; each list's hist, st
+// and sel zero); afterwards each list's sel/st describe its K-th largest
+// positive entry.
 static inline void radix_select(const RadixArgs* Ad, int nl, int64_t Nmax, hipStream_t s) {
     if (nl <= 0) return;
     const ctab<RadixArgs> A = ct(Ad);
     const unsigned hb = (unsigned)std::min<int64_t>(1024, std::max<int64_t>(1, cdiv(Nmax, 256 * 8)));
-    k_radix_init<<<nl, 256, 0, s>>>(A);
     for (int level = 0; level < RADIX_LEVELS; level++) {
         k_hist<<<dim3(hb, nl), 256, 0, s>>>(A, level);
         k_find<<<nl, 256, 0, s>>>(A, level);
