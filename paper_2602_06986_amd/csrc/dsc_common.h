@@ -262,16 +262,41 @@ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // ------------------------------------------------------- device helpers
 // Wave-wide sum in a fixed butterfly order; every lane returns lane 0's
 // result so that all lanes agree bit for bit.
+// Wave reductions (every lane active; every lane gets the result, combined
+// in a fixed order).  Within each row of 16 lanes, DPP lane permutations
+// (quad_perm [1,0,3,2] and [2,3,0,1], row_half_mirror, row_mirror) combine
+// lanes i and i^1, i^2, then the mirrored half and mirrored row, leaving the
+// row's result in all 16 lanes; the four row results are then read from
+// lanes 0, 16, 32 and 48.  This avoids a chain of LDS permutes.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+
+__device__ __forceinline__ double lane_f64(double v, int l) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(uint32_t)u, l);
+    const int hi = __builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return __shfl(v, 0, 64);
+    v += dpp_f64<0xB1>(v);       // quad_perm [1,0,3,2]
+    v += dpp_f64<0x4E>(v);       // quad_perm [2,3,0,1]
+    v += dpp_f64<0x141>(v);      // row_half_mirror
+    v += dpp_f64<0x140>(v);      // row_mirror
+    return (lane_f64(v, 0) + lane_f64(v, 16)) + (lane_f64(v, 32) + lane_f64(v, 48));
 }
 
 __device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return __shfl(v, 0, 64);
+    v = fmax(v, dpp_f64<0xB1>(v));
+    v = fmax(v, dpp_f64<0x4E>(v));
+    v = fmax(v, dpp_f64<0x141>(v));
+    v = fmax(v, dpp_f64<0x140>(v));
+    return fmax(fmax(lane_f64(v, 0), lane_f64(v, 16)), fmax(lane_f64(v, 32), lane_f64(v, 48)));
 }
 
 __host__ __device__ __forceinline__ int64_t choose2(int64_t m) { return m * (m - 1) / 2; }
