@@ -341,7 +341,8 @@ __device__ __forceinline__ unsigned long long wave_slot(unsigned long long* ctr)
 template <int TMAX>
 __device__ bool wave_exact_r(const Cand& c, const Ops& o, int n, int T,
                              const double* __restrict__ Yc, const double* __restrict__ syy,
-                             double* r, double* mean_out = nullptr, double* msq_out = nullptr) {
+                             double* r, double* mean_out = nullptr, double* msq_out = nullptr,
+                             double* __restrict__ vals = nullptr, double* sxx_out = nullptr) {
     const int lane = threadIdx.x & 63;
     double s = 0.0;
     int bad = 0;
@@ -351,6 +352,7 @@ __device__ bool wave_exact_r(const Cand& c, const Ops& o, int n, int T,
         const double f = cand_value(c, o, i);
         bad |= !isfinite(f);
         s += f;
+        if (vals) vals[i] = f;
         if (addsub) {
             const double a = o.Vf[(int64_t)c.ca * o.ldn + i];
             double b;
@@ -387,6 +389,7 @@ __device__ bool wave_exact_r(const Cand& c, const Ops& o, int n, int T,
         if (t < T) r[t] = wave_sum(sxy[t]) / sqrt(sxx * syy[t]);
     if (mean_out) *mean_out = m;
     if (msq_out) *msq_out = sxx / n + m * m;
+    if (sxx_out) *sxx_out = sxx;
     return true;
 }
 
@@ -1556,6 +1559,17 @@ __device__ __forceinline__ void d_compact(const double* __restrict__ sc, int64_t
 
 // Exact FP64 rescore of the pool (one wave per entry); also flags entries
 // whose ID is excluded.
+// Values of the first cap pool entries as the exact rescoring evaluated
+// them (row w of v, leading dimension ld), with their mean and centred sum
+// of squares (NaN where the candidate is not valid): the duplicate-pair
+// correlations then need one pass over two stored rows instead of two
+// evaluations of each candidate.
+struct PoolVals {
+    double* v;
+    int64_t ld, cap;
+    double *mean, *sxx;
+};
+
 template <int TMAX>
 __device__ __forceinline__ void d_rescore(const int64_t* __restrict__ pool,
                                                  const unsigned long long* __restrict__ Pp, int64_t cap,
@@ -1569,7 +1583,8 @@ __device__ __forceinline__ void d_rescore(const int64_t* __restrict__ pool,
                                                  const double* __restrict__ sc_row,
                                                  double* __restrict__ perr,
                                                  int32_t* __restrict__ rank,
-                                                 int32_t* __restrict__ order) {
+                                                 int32_t* __restrict__ order,
+                                                 const PoolVals pvs) {
     const int64_t P = min((int64_t)*Pp, cap);
     const int lane = threadIdx.x & 63;
     for (int64_t w = (int64_t)blockIdx.x * 4 + wave_id(); w < P; w += (int64_t)gridDim.x * 4) {
@@ -1577,7 +1592,14 @@ __device__ __forceinline__ void d_rescore(const int64_t* __restrict__ pool,
     Cand c;
     bool ok = cand_of_id(ev, id, c);
     double r[TMAX];
-    ok = ok && wave_exact_r<TMAX>(c, o, n, T, Yc, syy, r);
+    const bool keep = w < pvs.cap;
+    double m = 0.0, sxx = 0.0;
+    ok = ok && wave_exact_r<TMAX>(c, o, n, T, Yc, syy, r, &m, nullptr, keep ? pvs.v + w * pvs.ld : nullptr,
+                                  &sxx);
+    if (keep && lane == 0) {                              // NaN: nothing stored for this entry
+        pvs.mean[w] = ok ? m : __longlong_as_double(0x7FF8000000000000LL);
+        pvs.sxx[w] = ok ? sxx : __longlong_as_double(0x7FF8000000000000LL);
+    }
     int ex = 0;
     for (int e = lane; e < n_excl; e += 64) ex |= excl[e] == id;
     ex = __any(ex);
@@ -1764,29 +1786,48 @@ __device__ __forceinline__ void d_scan_offsets(const int32_t* __restrict__ cnt,
 }
 
 // One wave per near-tie pair (earlier position lo[q]+k, later position q):
-// duplicate flag = |corr| >= 1 - TAU_DUP.
+// duplicate flag = |corr| >= 1 - TAU_DUP.  Pairs of stored pool entries
+// take the stored values, means and sums of squares (the same numbers the
+// two-pass evaluation below forms, in the same order); others evaluate
+// both candidates.
 __device__ __forceinline__ void d_pairs(const int64_t* __restrict__ pool,
                                                const int32_t* __restrict__ order,
                                                const int32_t* __restrict__ lo,
                                                const int64_t* __restrict__ off,
                                                const unsigned long long* __restrict__ Pp, int64_t cap,
                                                const EvalCtx& ev, Ops o, int n,
-                                               uint8_t* __restrict__ flag, int64_t flag_cap) {
+                                               uint8_t* __restrict__ flag, int64_t flag_cap,
+                                               const PoolVals pvs) {
     const int64_t P = min((int64_t)*Pp, cap);
     const int64_t total = min(off[P], flag_cap);
     const int lane = threadIdx.x & 63;
     for (int64_t w = (int64_t)blockIdx.x * 4 + wave_id(); w < total;
          w += (int64_t)gridDim.x * 4) {
-    // find q with off[q] <= w < off[q+1]
+    // find q with off[q] <= w < off[q+1]: 64 probes per round, the last
+    // probe at or below w narrows [a, b) to one probe step
     int64_t a = 0, b = P;
     while (b - a > 1) {
-        const int64_t mid = (a + b) / 2;
-        if (off[mid] <= w) a = mid; else b = mid;
+        const int64_t step = (b - a + 63) / 64;
+        const int64_t idx = a + lane * step;
+        const uint64_t le = __builtin_amdgcn_ballot_w64(idx < b && off[idx] <= w);
+        a += (int64_t)(63 - __clzll((long long)le)) * step;
+        b = min(b, a + step);
     }
     const int64_t q = a;
     const int64_t pe = lo[q] + (w - off[q]);
+    const int32_t iu = order[pe], iv = order[q];
+    if (iu < pvs.cap && iv < pvs.cap && !isnan(pvs.sxx[iu]) && !isnan(pvs.sxx[iv])) {
+        const double* u = pvs.v + (int64_t)iu * pvs.ld;
+        const double* v = pvs.v + (int64_t)iv * pvs.ld;
+        const double mu_ = pvs.mean[iu], mv = pvs.mean[iv];
+        double uv = 0.0;
+        for (int i = lane; i < n; i += 64) uv += (u[i] - mu_) * (v[i] - mv);
+        uv = wave_sum(uv);
+        if (lane == 0) flag[w] = fabs(uv) / sqrt(pvs.sxx[iu] * pvs.sxx[iv]) >= 1.0 - TAU_DUP;
+        continue;
+    }
     Cand cu, cv;
-    const bool okp = cand_of_id(ev, pool[order[pe]], cu) && cand_of_id(ev, pool[order[q]], cv);
+    const bool okp = cand_of_id(ev, pool[iu], cu) && cand_of_id(ev, pool[iv], cv);
     if (!okp) {
         if (lane == 0) flag[w] = 0;
         continue;
@@ -2177,6 +2218,7 @@ struct SelArgs {
     int64_t* out_ids;
     double* out_sc;
     int64_t* res;
+    PoolVals pvs;             // stored values of the first pvs.cap pool entries
 };
 
 // grid (blocks, lists) for the streaming kernels, (lists) for the one-block ones
@@ -2190,7 +2232,7 @@ __global__ __launch_bounds__(256) void k_rescore(ctab<SelArgs> A) {
     const SelArgs& a = tab(A, blockIdx.y);
     DSC_GLOBAL(a.sc); DSC_GLOBAL(a.sel); DSC_GLOBAL(a.st); DSC_GLOBAL(a.pool); DSC_GLOBAL(a.cnt); DSC_GLOBAL(a.ev.raw2c); DSC_GLOBAL(a.ev.valid); DSC_GLOBAL(a.o.Vf); DSC_GLOBAL(a.o.Rf); DSC_GLOBAL(a.Yc); DSC_GLOBAL(a.syy); DSC_GLOBAL(a.ps); DSC_GLOBAL(a.pex); DSC_GLOBAL(a.maxerr); DSC_GLOBAL(a.order); DSC_GLOBAL(a.lo); DSC_GLOBAL(a.wc); DSC_GLOBAL(a.off); DSC_GLOBAL(a.flag); DSC_GLOBAL(a.parent); DSC_GLOBAL(a.blk); DSC_GLOBAL(a.repid); DSC_GLOBAL(a.reppos); DSC_GLOBAL(a.headpos); DSC_GLOBAL(a.out_ids); DSC_GLOBAL(a.out_sc); DSC_GLOBAL(a.res);
     d_rescore<DISCOVER_MAX_TARGETS>(a.pool, a.cnt, a.cap, a.ev, a.o, a.n, a.T, a.mode, a.t, a.Yc, a.syy,
-                                    a.excl, a.n_excl, a.ps, a.pex, a.sc, a.perr, a.rank, a.order);
+                                    a.excl, a.n_excl, a.ps, a.pex, a.sc, a.perr, a.rank, a.order, a.pvs);
 }
 
 // grid (i tiles, j chunks, lists)
@@ -2222,7 +2264,7 @@ __global__ __launch_bounds__(256) void k_pairs(ctab<SelArgs> A) {
     const SelArgs& a = tab(A, blockIdx.y);
     DSC_GLOBAL(a.sc); DSC_GLOBAL(a.sel); DSC_GLOBAL(a.st); DSC_GLOBAL(a.pool); DSC_GLOBAL(a.cnt); DSC_GLOBAL(a.ev.raw2c); DSC_GLOBAL(a.ev.valid); DSC_GLOBAL(a.o.Vf); DSC_GLOBAL(a.o.Rf); DSC_GLOBAL(a.Yc); DSC_GLOBAL(a.syy); DSC_GLOBAL(a.ps); DSC_GLOBAL(a.pex); DSC_GLOBAL(a.maxerr); DSC_GLOBAL(a.order); DSC_GLOBAL(a.lo); DSC_GLOBAL(a.wc); DSC_GLOBAL(a.off); DSC_GLOBAL(a.flag); DSC_GLOBAL(a.parent); DSC_GLOBAL(a.blk); DSC_GLOBAL(a.repid); DSC_GLOBAL(a.reppos); DSC_GLOBAL(a.headpos); DSC_GLOBAL(a.out_ids); DSC_GLOBAL(a.out_sc); DSC_GLOBAL(a.res);
     if (!a.dedup) return;
-    d_pairs(a.pool, a.order, a.lo, a.off, a.cnt, a.cap, a.ev, a.o, a.n, a.flag, a.fcap);
+    d_pairs(a.pool, a.order, a.lo, a.off, a.cnt, a.cap, a.ev, a.o, a.n, a.flag, a.fcap, a.pvs);
 }
 
 __global__ __launch_bounds__(GRP_THREADS) void k_groups(ctab<SelArgs> A) {
@@ -2569,8 +2611,15 @@ struct Problem {
 struct ListState {
     int b, t;
     int64_t K, cap, fcap;
+    int n = 0;                // samples of the list's problem
     bool done = false;
 };
+
+// Pool entries whose values the rescoring keeps for the duplicate pairs:
+// up to 16 MB of values per list.
+static int64_t pool_vals_cap(int64_t cap, int n) {
+    return std::min<int64_t>(cap, ((int64_t)16 << 20) / (8 * (int64_t)std::max(n, 1)));
+}
 
 // Allocate every problem's working memory for one call.
 static void layout_problems(discover_ctx* ctx, const discover_problem* probs, int nb,
@@ -2977,6 +3026,10 @@ static void select_round(discover_ctx* ctx, const discover_problem* probs,
         v.push_back(ar.add(64));                   // res
         v.push_back(ar.add(64));                   // cnt, maxerr, st[2], sel[4]
         v.push_back(ar.add(4096 * 4));             // hist
+        const size_t pvc = (size_t)pool_vals_cap(L.cap, L.n);
+        v.push_back(ar.add(pvc * (size_t)L.n * 8)); // stored pool values
+        v.push_back(ar.add(pvc * 8));              // their means
+        v.push_back(ar.add(pvc * 8));              // their centred sums of squares
     }
     char* base = (char*)ctx->raw("sel_arena" + ctx->tag, ar.total);
     sa.assign(nl, SelArgs{});
@@ -2999,6 +3052,8 @@ static void select_round(discover_ctx* ctx, const discover_problem* probs,
         a.reppos = (int32_t*)at(); a.headpos = (int32_t*)at(); a.res = (int64_t*)at();
         char* misc = at();
         uint32_t* hist = (uint32_t*)at();
+        a.pvs.v = (double*)at(); a.pvs.mean = (double*)at(); a.pvs.sxx = (double*)at();
+        a.pvs.ld = L.n; a.pvs.cap = pool_vals_cap(L.cap, L.n);
         a.cnt = (unsigned long long*)misc;
         a.maxerr = (unsigned long long*)(misc + 8);
         int64_t* stv = (int64_t*)(misc + 16);
@@ -3071,9 +3126,11 @@ static void select_reserve(discover_ctx* ctx, const discover_screen_params& prm,
     Arena ar;
     for (const ListState& L : LS) {
         const size_t cap = (size_t)L.cap, fcap = (size_t)L.fcap;
+        const size_t pvc = (size_t)pool_vals_cap(L.cap, L.n);
         for (size_t b : {cap * 8, cap * 8, cap, cap * 4, cap * 4, cap * 4, cap * 4, cap * 8, cap * 8, (cap + 1) * 8, fcap,
                          (cap + 1) * 4, (cap + 1) * 4, (cap + 1) * 8, (cap + 1) * 4,
-                         ((size_t)prm.k + 1) * 4, (size_t)64, (size_t)64, (size_t)4096 * 4})
+                         ((size_t)prm.k + 1) * 4, (size_t)64, (size_t)64, (size_t)4096 * 4,
+                         pvc * (size_t)L.n * 8, pvc * 8, pvc * 8})
             ar.add(b);
     }
     ctx->raw("sel_arena" + ctx->tag, ar.total);
@@ -3151,7 +3208,7 @@ void generate_screen(discover_ctx* ctx, const discover_problem* probs, int nb,
         }
         for (int t = 0; t < P.Tl; t++) {
             ListState L;
-            L.b = b; L.t = t;
+            L.b = b; L.t = t; L.n = P.n;
             L.K = 2 * (int64_t)prm.k + probs[b].n_exclude + 64;
             L.cap = 4 * L.K + 4096;
             L.fcap = 64 * L.cap;
