@@ -571,8 +571,9 @@ struct BandArgs {
     const int2* items;
     int64_t n_lanes;
     const double* lane_q;
-    const uint32_t* sel;
-    const int64_t* st;
+    uint32_t* sel;            // radix selection of the problem's lanes
+    int64_t* st;
+    const uint32_t* hist;     // its two level histograms
     int4* band;
     unsigned long long* bcnt;
     int64_t bcap;
@@ -591,11 +592,12 @@ struct BandArgs {
 // subsets whose exact q is at least that value minus SW3_RCP_DELTA, so the
 // threshold drops by it; and a lane whose exact best reaches the threshold
 // shows a sweep value no lower than threshold - SW3_RCP_DELTA.
-__device__ __forceinline__ double band_thr(const BandArgs& g) {
-    if (g.st[1]) return -0.5;                            // fewer than m valid lanes: take all
-    return select_threshold(g.sel, g.st) * (1.0 - 1e-12) - GRAM_DELTA -
-           (g.D == 3 ? SW3_RCP_DELTA : 0.0);
+__device__ __forceinline__ double band_thr(const uint32_t* sel, const int64_t* st, int D) {
+    if (st[1]) return -0.5;                              // fewer than m valid lanes: take all
+    return select_threshold(sel, st) * (1.0 - 1e-12) - GRAM_DELTA - (D == 3 ? SW3_RCP_DELTA : 0.0);
 }
+
+__device__ __forceinline__ double band_thr(const BandArgs& g) { return band_thr(g.sel, g.st, g.D); }
 
 __device__ __forceinline__ void band_push(const BandArgs& g, int a, int b, int c) {
     const unsigned long long slot = atomicAdd(g.bcnt, 1ull);
@@ -605,8 +607,11 @@ __device__ __forceinline__ void band_push(const BandArgs& g, int a, int b, int c
 // grid (blocks, problems)
 __global__ __launch_bounds__(256) void k_band_lanes(ctab<BandArgs> A) {
     const BandArgs& g = tab(A, blockIdx.y);
-    DSC_GLOBAL(g.lane_q); DSC_GLOBAL(g.items); DSC_GLOBAL(g.items3); DSC_GLOBAL(g.sel); DSC_GLOBAL(g.st); DSC_GLOBAL(g.band); DSC_GLOBAL(g.bcnt); DSC_GLOBAL(g.pairs); DSC_GLOBAL(g.pcnt); DSC_GLOBAL(g.lidx); DSC_GLOBAL(g.lval); DSC_GLOBAL(g.lcnt);
-    const double thr = band_thr(g);
+    DSC_GLOBAL(g.lane_q); DSC_GLOBAL(g.items); DSC_GLOBAL(g.items3); DSC_GLOBAL(g.sel); DSC_GLOBAL(g.st); DSC_GLOBAL(g.band); DSC_GLOBAL(g.bcnt); DSC_GLOBAL(g.pairs); DSC_GLOBAL(g.pcnt); DSC_GLOBAL(g.lidx); DSC_GLOBAL(g.lval); DSC_GLOBAL(g.lcnt); DSC_GLOBAL(g.hist);
+    uint32_t sel[3];
+    int64_t st[2];
+    radix_finish(g.hist, g.sel, g.st, sel, st);
+    const double thr = band_thr(sel, st, g.D);
     const int per = g.D == 3 ? 4 * SW3_A * 64 : 64;
     const int64_t nl = g.lidx ? min((int64_t)*g.lcnt, g.n_lanes) : g.n_lanes;
     for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < nl; e += (int64_t)gridDim.x * 256) {
@@ -1147,7 +1152,7 @@ static size_t band_arena_bytes(const std::vector<int>& act, const std::vector<in
         v.push_back(br.add(c));                                        // taken
         v.push_back(br.add((size_t)m * 4));                            // chosen
         v.push_back(br.add(64));                                       // bcnt, pcnt, st[2], sel[4]
-        v.push_back(br.add(4096 * 4));                                 // hist
+        v.push_back(br.add(8192 * 4));                                 // hist (two levels)
         if (offs) offs->push_back(v);
     }
     return br.total;
@@ -1315,7 +1320,7 @@ void l0_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D
             g.items = sa[b].items; g.items3 = sa[b].items3;
             g.n_lanes = ni[b] * per;
             g.lane_q = sa[b].lane_q;
-            g.sel = (uint32_t*)(misc + 32); g.st = (int64_t*)(misc + 16);
+            g.sel = (uint32_t*)(misc + 32); g.st = (int64_t*)(misc + 16); g.hist = (const uint32_t*)(bb + v[7]);
             g.band = (int4*)(bb + v[0]); g.bcnt = (unsigned long long*)misc; g.bcap = cap[b];
             g.pairs = (int4*)(bb + v[1]); g.pcnt = (unsigned long long*)misc + 1; g.pcap = cap[b];
             g.theta = pa[b].theta;
@@ -1323,7 +1328,7 @@ void l0_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D
             ra[q] = RadixArgs{g.lidx ? g.lval : g.lane_q, g.n_lanes, m, (uint32_t*)(bb + v[7]),
                               (uint32_t*)(misc + 32), (int64_t*)(misc + 16), g.lidx ? g.lcnt : nullptr};
             fills.push_back(fill_seg(misc, 48, 0u));              // bcnt, pcnt, st, sel
-            fills.push_back(fill_seg(bb + v[7], 4096 * 4, 0u));   // radix histogram
+            fills.push_back(fill_seg(bb + v[7], 8192 * 4, 0u));   // radix histograms
             lanes_max = std::max(lanes_max, g.n_lanes);
             RefitArgs& f = fa[q];
             f = RefitArgs{};

@@ -1531,10 +1531,14 @@ __global__ __launch_bounds__(256) void k_screen_lp1(PairArgs g, const void* __re
 // ------------------------------------------------------------ selection
 // Pool = every candidate whose score may reach theta - margin.
 __device__ __forceinline__ void d_compact(const double* __restrict__ sc, int64_t N,
-                                                 const uint32_t* __restrict__ sel,
-                                                 const int64_t* __restrict__ st, double margin,
+                                                 const uint32_t* __restrict__ hist,
+                                                 uint32_t* __restrict__ gsel,
+                                                 int64_t* __restrict__ gst, double margin,
                                                  int64_t cap, int64_t* __restrict__ pool,
                                                  unsigned long long* __restrict__ cnt) {
+    uint32_t sel[3];
+    int64_t st[2];
+    radix_finish(hist, gsel, gst, sel, st);
     const double th = select_threshold(sel, st);
     const double lo = st[1] ? 0.0 : th - 2.0 * margin;
     // one atomic per wave: lanes take consecutive slots in lane order
@@ -1735,16 +1739,36 @@ __device__ __forceinline__ void d_window(const double* __restrict__ ss,
                                          const unsigned long long* __restrict__ Pp, int64_t cap,
                                          int32_t* __restrict__ lo, int32_t* __restrict__ cnt) {
     const int64_t P = min((int64_t)*Pp, cap);
+    // The window of q is the run of earlier positions l' (at most 1024 back)
+    // whose scores pass sp - s <= TAU_NEAR * sp.  Scores descend, and for
+    // s <= sp <= 2 s the difference is exact, so the test holds on a suffix
+    // of positions before q: a galloping search (1, 2, 4, ... back) brackets
+    // its start and a bisection finds it, in O(log window) loads.
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < P;
          q += (int64_t)gridDim.x * blockDim.x) {
         const double s = ss[q];
         int64_t l = q;
-        if (s > 0.0)
-            while (l > 0 && q - l < 1024) {
-                const double sp = ss[l - 1];
-                if (!(sp - s <= TAU_NEAR * sp)) break;
-                l--;
+        if (s > 0.0) {
+            const int64_t lim = q >= 1024 ? q - 1024 : 0;
+            int64_t good = q, bad = lim - 1;          // the test holds on [good, q), fails at bad
+            for (int64_t step = 1;; step *= 2) {
+                const int64_t c = q - step;
+                if (c < lim) break;
+                const double sp = ss[c];
+                if (sp - s <= TAU_NEAR * sp) {
+                    good = c;
+                } else {
+                    bad = c;
+                    break;
+                }
             }
+            while (good - bad > 1) {
+                const int64_t mid = bad + (good - bad) / 2;
+                const double sp = ss[mid];
+                if (sp - s <= TAU_NEAR * sp) good = mid; else bad = mid;
+            }
+            l = good;
+        }
         lo[q] = (int32_t)l;
         cnt[q] = (int32_t)(q - l);
     }
@@ -2191,8 +2215,9 @@ __global__ __launch_bounds__(256) void k_fixup(ctab<FixArgs> A) {
 struct SelArgs {
     const double* sc;         // score slots of the list
     int64_t N;
-    const uint32_t* sel;      // radix selection of the list
-    const int64_t* st;
+    uint32_t* sel;            // radix selection of the list
+    int64_t* st;
+    const uint32_t* hist;     // its two level histograms
     double margin;
     int64_t cap, fcap;        // pool and duplicate-pair capacities
     int64_t* pool;
@@ -2225,7 +2250,7 @@ struct SelArgs {
 __global__ __launch_bounds__(256) void k_compact(ctab<SelArgs> A) {
     const SelArgs& a = tab(A, blockIdx.y);
     DSC_GLOBAL(a.sc); DSC_GLOBAL(a.sel); DSC_GLOBAL(a.st); DSC_GLOBAL(a.pool); DSC_GLOBAL(a.cnt); DSC_GLOBAL(a.ev.raw2c); DSC_GLOBAL(a.ev.valid); DSC_GLOBAL(a.o.Vf); DSC_GLOBAL(a.o.Rf); DSC_GLOBAL(a.Yc); DSC_GLOBAL(a.syy); DSC_GLOBAL(a.ps); DSC_GLOBAL(a.pex); DSC_GLOBAL(a.maxerr); DSC_GLOBAL(a.order); DSC_GLOBAL(a.lo); DSC_GLOBAL(a.wc); DSC_GLOBAL(a.off); DSC_GLOBAL(a.flag); DSC_GLOBAL(a.parent); DSC_GLOBAL(a.blk); DSC_GLOBAL(a.repid); DSC_GLOBAL(a.reppos); DSC_GLOBAL(a.headpos); DSC_GLOBAL(a.out_ids); DSC_GLOBAL(a.out_sc); DSC_GLOBAL(a.res);
-    d_compact(a.sc, a.N, a.sel, a.st, a.margin, a.cap, a.pool, a.cnt);
+    d_compact(a.sc, a.N, a.hist, a.sel, a.st, a.margin, a.cap, a.pool, a.cnt);
 }
 
 __global__ __launch_bounds__(256) void k_rescore(ctab<SelArgs> A) {
@@ -3025,7 +3050,7 @@ static void select_round(discover_ctx* ctx, const discover_problem* probs,
         v.push_back(ar.add(((size_t)k + 1) * 4));  // headpos
         v.push_back(ar.add(64));                   // res
         v.push_back(ar.add(64));                   // cnt, maxerr, st[2], sel[4]
-        v.push_back(ar.add(4096 * 4));             // hist
+        v.push_back(ar.add(8192 * 4));             // hist (two levels)
         const size_t pvc = (size_t)pool_vals_cap(L.cap, L.n);
         v.push_back(ar.add(pvc * (size_t)L.n * 8)); // stored pool values
         v.push_back(ar.add(pvc * 8));              // their means
@@ -3058,7 +3083,7 @@ static void select_round(discover_ctx* ctx, const discover_problem* probs,
         a.maxerr = (unsigned long long*)(misc + 8);
         int64_t* stv = (int64_t*)(misc + 16);
         uint32_t* sel = (uint32_t*)(misc + 32);
-        a.sel = sel; a.st = stv;
+        a.sel = sel; a.st = stv; a.hist = hist;
         a.sc = P.scores + (int64_t)L.t * P.N; a.N = P.N;
         a.margin = margin[L.b]; a.cap = L.cap; a.fcap = L.fcap;
         a.ev = P.ev(); a.o = P.ops(); a.n = P.n; a.T = P.T; a.mode = prm.score_mode; a.t = L.t;
@@ -3069,7 +3094,7 @@ static void select_round(discover_ctx* ctx, const discover_problem* probs,
         a.out_sc = outs[L.b].sc + (int64_t)L.t * k;
         ra[q] = RadixArgs{a.sc, P.N, L.K, hist, sel, stv, nullptr};
         fills.push_back(fill_seg(misc, 48, 0u));            // pool count, maximum error, st, sel
-        fills.push_back(fill_seg(hist, 4096 * 4, 0u));
+        fills.push_back(fill_seg(hist, 8192 * 4, 0u));
         Nmax = std::max(Nmax, P.N);
         capmax = std::max(capmax, L.cap);
         Kmax = std::max(Kmax, L.K);
@@ -3129,7 +3154,7 @@ static void select_reserve(discover_ctx* ctx, const discover_screen_params& prm,
         const size_t pvc = (size_t)pool_vals_cap(L.cap, L.n);
         for (size_t b : {cap * 8, cap * 8, cap, cap * 4, cap * 4, cap * 4, cap * 4, cap * 8, cap * 8, (cap + 1) * 8, fcap,
                          (cap + 1) * 4, (cap + 1) * 4, (cap + 1) * 8, (cap + 1) * 4,
-                         ((size_t)prm.k + 1) * 4, (size_t)64, (size_t)64, (size_t)4096 * 4,
+                         ((size_t)prm.k + 1) * 4, (size_t)64, (size_t)64, (size_t)8192 * 4,
                          pvc * (size_t)L.n * 8, pvc * 8, pvc * 8})
             ar.add(b);
     }

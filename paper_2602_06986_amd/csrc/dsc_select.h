@@ -23,11 +23,14 @@ static __device__ __forceinline__ uint64_t fx_key(double x) {
 }
 
 // One radix selection per list: x[0..N) holds the values (entries <= 0 are
-// ignored), K the rank wanted; hist is a 4096-bin scratch histogram, sel
-// the selected 12-bit digits (sel[2] stays 0), st[0] the remaining rank and
-// st[1] the take-all flag (fewer than K positive entries).  Before the
-// selection, hist, st and sel must be zero (the callers clear them with
-// their other counters, which saves a launch).
+// ignored), K the rank wanted; hist holds two 4096-bin histograms (one per
+// level), sel the selected 12-bit digits (sel[2] stays 0), st[0] the
+// remaining rank and st[1] the take-all flag (fewer than K positive
+// entries).  Before the selection, hist, st and sel must be zero (the
+// callers clear them with their other counters).  A level's digit is read
+// from its finished histogram by every block of the next kernel (the
+// level-1 histogram for level 0, the selection's consumer for level 1), so
+// no launch is spent on it; block 0 of that kernel publishes it.
 struct RadixArgs {
     const double* x;
     int64_t N;
@@ -38,42 +41,20 @@ struct RadixArgs {
     const unsigned long long* Nd;   // or NULL: device count of entries (at most N)
 };
 
-// grid (blocks, lists)
-static __global__ __launch_bounds__(256) void k_hist(ctab<RadixArgs> A, int level) {
-    const RadixArgs& a = tab(A, blockIdx.y);
-    DSC_GLOBAL(a.x); DSC_GLOBAL(a.hist); DSC_GLOBAL(a.sel); DSC_GLOBAL(a.Nd);
-    __shared__ uint32_t h[4096];
-    for (int b = threadIdx.x; b < 4096; b += 256) h[b] = 0;
-    __syncthreads();
-    uint32_t p0 = 0, p1 = 0;
-    if (level > 0) p0 = a.sel[0];
-    if (level > 1) p1 = a.sel[1];
-    const double* __restrict__ sc = a.x;
-    const int64_t N = a.Nd ? min((int64_t)*a.Nd, a.N) : a.N;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256) {
-        const double x = sc[i];
-        if (!(x > 0.0)) continue;
-        const uint64_t u = fx_key(x);
-        if (level > 0 && ((u >> 40) & 0xFFF) != p0) continue;
-        if (level > 1 && ((u >> 28) & 0xFFF) != p1) continue;
-        atomicAdd(&h[(u >> (40 - 12 * level)) & 0xFFF], 1u);
-    }
-    __syncthreads();
-    for (int b = threadIdx.x; b < 4096; b += 256)
-        if (h[b]) atomicAdd(&a.hist[b], h[b]);
-}
+struct RadixDigit {
+    uint32_t digit;
+    int64_t rank;                   // rank left within the digit's bin
+    bool all;                       // fewer than the wanted rank: take all
+};
 
-// One block of 256 threads per list: thread t owns bins [16t, 16t+16); a
-// suffix scan over threads gives the count above each range.  The
-// histogram is cleared for the next level after it has been read.  Level 0
-// starts from rank K, later levels from the rank left in st[0].
-static __global__ __launch_bounds__(256) void k_find(ctab<RadixArgs> A, int level) {
-    const RadixArgs& a = tab(A, blockIdx.x);
-    DSC_GLOBAL(a.hist); DSC_GLOBAL(a.sel); DSC_GLOBAL(a.st);
-    uint32_t* __restrict__ hist = a.hist;
-    uint32_t* __restrict__ sel = a.sel;
-    int64_t* __restrict__ st = a.st;
+// The digit holding rank K of a finished histogram, by the 256 threads of a
+// block (every thread gets it): thread t owns bins [16t, 16t+16) and a
+// suffix scan over threads gives the count above each range.
+static __device__ __forceinline__ RadixDigit radix_digit(const uint32_t* __restrict__ hist, int64_t K,
+                                                         bool all_in) {
     __shared__ int64_t part[256];
+    __shared__ uint32_t s_digit;
+    __shared__ int64_t s_rank;
     const int t = threadIdx.x;
     int64_t loc = 0;
     uint32_t hb[16];
@@ -81,8 +62,11 @@ static __global__ __launch_bounds__(256) void k_find(ctab<RadixArgs> A, int leve
         hb[q] = hist[t * 16 + q];
         loc += hb[q];
     }
-    for (int q = 0; q < 16; q++) hist[t * 16 + q] = 0;
     part[t] = loc;
+    if (t == 0) {
+        s_digit = 0;
+        s_rank = K;
+    }
     __syncthreads();
     // inclusive suffix sums (Hillis-Steele over 256 entries)
     for (int o = 1; o < 256; o <<= 1) {
@@ -91,28 +75,74 @@ static __global__ __launch_bounds__(256) void k_find(ctab<RadixArgs> A, int leve
         part[t] += v;
         __syncthreads();
     }
-    const int64_t K = level == 0 ? a.K : st[0];
-    const int64_t total = part[0];
-    const bool all = (level > 0 && st[1] != 0) || total < K;
-    __syncthreads();
-    if (all) {
-        if (t == 0) {
-            st[1] = 1;
-            sel[level] = 0;
-        }
-        return;
-    }
+    const bool all = all_in || part[0] < K;
     const int64_t above = t + 1 < 256 ? part[t + 1] : 0;     // count in bins above my range
-    if (above < K && above + loc >= K) {                      // exactly one thread
+    if (!all && above < K && above + loc >= K) {              // exactly one thread
         int64_t cum = above;
         for (int q = 15; q >= 0; q--) {
             if (cum + hb[q] >= K) {
-                sel[level] = (uint32_t)(t * 16 + q);
-                st[0] = K - cum;
+                s_digit = (uint32_t)(t * 16 + q);
+                s_rank = K - cum;
                 break;
             }
             cum += hb[q];
         }
+    }
+    __syncthreads();
+    const RadixDigit r{s_digit, s_rank, all};
+    __syncthreads();                                          // part and s_* free again
+    return r;
+}
+
+// grid (blocks, lists).  Level 1 first reads the level-0 digit.
+static __global__ __launch_bounds__(256) void k_hist(ctab<RadixArgs> A, int level) {
+    const RadixArgs& a = tab(A, blockIdx.y);
+    DSC_GLOBAL(a.x); DSC_GLOBAL(a.hist); DSC_GLOBAL(a.sel); DSC_GLOBAL(a.st); DSC_GLOBAL(a.Nd);
+    __shared__ uint32_t h[4096];
+    uint32_t p0 = 0;
+    if (level == 1) {
+        const RadixDigit d0 = radix_digit(a.hist, a.K, false);
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            a.sel[0] = d0.digit;
+            a.st[0] = d0.rank;
+            a.st[1] = d0.all ? 1 : 0;
+        }
+        if (d0.all) return;                               // (block-uniform) nothing left to split
+        p0 = d0.digit;
+    }
+    for (int b = threadIdx.x; b < 4096; b += 256) h[b] = 0;
+    __syncthreads();
+    const double* __restrict__ sc = a.x;
+    const int64_t N = a.Nd ? min((int64_t)*a.Nd, a.N) : a.N;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256) {
+        const double x = sc[i];
+        if (!(x > 0.0)) continue;
+        const uint64_t u = fx_key(x);
+        if (level == 1 && ((u >> 40) & 0xFFF) != p0) continue;
+        atomicAdd(&h[(u >> (40 - 12 * level)) & 0xFFF], 1u);
+    }
+    __syncthreads();
+    uint32_t* hout = a.hist + level * 4096;
+    for (int b = threadIdx.x; b < 4096; b += 256)
+        if (h[b]) atomicAdd(&hout[b], h[b]);
+}
+
+// The selection's consumer: every block reads the level-1 digit into sel
+// and st (its own copies); block 0 publishes them for later kernels.
+static __device__ __forceinline__ void radix_finish(const uint32_t* __restrict__ hist,
+                                                    uint32_t* __restrict__ gsel, int64_t* __restrict__ gst,
+                                                    uint32_t (&sel)[3], int64_t (&st)[2]) {
+    const bool all0 = gst[1] != 0;
+    const RadixDigit d1 = radix_digit(hist + 4096, gst[0], all0);
+    sel[0] = gsel[0];
+    sel[1] = d1.all ? 0u : d1.digit;
+    sel[2] = 0u;
+    st[0] = d1.rank;
+    st[1] = d1.all ? 1 : 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        gsel[1] = sel[1];
+        gst[0] = st[0];
+        gst[1] = st[1];
     }
 }
 
@@ -122,17 +152,14 @@ static __device__ __forceinline__ double select_threshold(const uint32_t* sel, c
     return (double)key * 2.220446049250313e-16;          // * 2^-52 (exact)
 }
 
-// Launch the selections of nl lists (device table A; each list's hist, st
-// and sel zero); afterwards each list's sel/st describe its K-th largest
-// positive entry.
+// Launch the histograms of the selections of nl lists (device table A;
+// each list's hist, st and sel zero); the consumer's radix_finish then
+// gives the K-th largest positive entry of each list.
 static inline void radix_select(const RadixArgs* Ad, int nl, int64_t Nmax, hipStream_t s) {
     if (nl <= 0) return;
     const ctab<RadixArgs> A = ct(Ad);
     const unsigned hb = (unsigned)std::min<int64_t>(1024, std::max<int64_t>(1, cdiv(Nmax, 256 * 8)));
-    for (int level = 0; level < RADIX_LEVELS; level++) {
-        k_hist<<<dim3(hb, nl), 256, 0, s>>>(A, level);
-        k_find<<<nl, 256, 0, s>>>(A, level);
-    }
+    for (int level = 0; level < RADIX_LEVELS; level++) k_hist<<<dim3(hb, nl), 256, 0, s>>>(A, level);
     check_launch("radix_select");
 }
 
