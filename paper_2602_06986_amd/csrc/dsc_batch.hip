@@ -87,8 +87,14 @@ static void sisso_sequence(discover_ctx* ctx, const SissoCall& c, const std::str
     std::vector<ListCheck> lc;
     std::vector<BandCheck> bc;
     std::vector<discover_l0_stats> l0st(nb);
+    ctx->ops_tag = gtag;                  // the operand features are made once, by d = 1
+    struct OpsScope {                     // no reuse outside this sequence, also on an error
+        discover_ctx* c;
+        ~OpsScope() { c->ops_reuse = false; c->ops_tag.clear(); }
+    } ops_scope{ctx};
     for (int d = 1; d <= D; d++) {
         ctx->tag = gtag + "d" + std::to_string(d);
+        ctx->ops_reuse = d > 1;
         std::vector<discover_problem> sp(c.probs, c.probs + nb);
         std::vector<ScreenOut> so(nb);
         for (int b = 0; b < nb; b++) {
@@ -121,6 +127,7 @@ static void sisso_sequence(discover_ctx* ctx, const SissoCall& c, const std::str
         }
         l0_batch(ctx, lp.data(), nb, d, m, lo, l0st, st, ctx->capturing ? &bc : nullptr);
     }
+    ctx->ops_reuse = false;
     if (c.omp_D > D) {
         // the best D-model of each dataset, extended by OMP over its subspace
         ctx->tag = gtag + "omp";

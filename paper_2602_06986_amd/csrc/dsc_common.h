@@ -101,6 +101,14 @@ struct discover_ctx {
     // Suffix of argument-table and result-buffer names, so that the calls of
     // one captured sequence keep tables of their own.
     std::string tag;
+    // Operand features of a screen (values, reciprocals, centred copies,
+    // their moments and sample-major copies) depend on X alone: a sequence
+    // of screens over the same problems keeps them in an arena named by
+    // ops_tag and, with ops_reuse set, skips materialising them again when
+    // the problems' layout signature matches the one stored in ops_sig.
+    std::string ops_tag;
+    bool ops_reuse = false;
+    std::vector<int64_t> ops_sig;
     // Bumped whenever device memory that a captured graph may reference is
     // released (a buffer regrown, plans evicted); graphs of an older
     // generation are discarded instead of replayed.

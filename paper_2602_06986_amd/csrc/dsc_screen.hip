@@ -2650,8 +2650,8 @@ static int64_t pool_vals_cap(int64_t cap, int n) {
 static void layout_problems(discover_ctx* ctx, const discover_problem* probs, int nb,
                             const discover_screen_params& prm, std::vector<Problem>& PS) {
     PS.resize(nb);
-    Arena ar;
-    std::vector<std::vector<size_t>> o(nb);
+    Arena ar, ao;                                 // per call / operand features
+    std::vector<std::vector<size_t>> o(nb), oo(nb);
     for (int b = 0; b < nb; b++) {
         const discover_problem& pb = probs[b];
         Problem& P = PS[b];
@@ -2670,9 +2670,11 @@ static void layout_problems(discover_ctx* ctx, const discover_problem* probs, in
         P.pairs = sp.streamed && (pl.dense_ops || pl.list_ops);
         const size_t Mc = P.Mc, ldn = P.ldn, n = P.n, ldm = P.ldm;
         auto& v = o[b];
-        for (int k = 0; k < 3; k++) v.push_back(ar.add(Mc * ldn * 8));          // Vf Rf Cf
-        for (int k = 0; k < 3; k++) v.push_back(ar.add(Mc * 8));                // mu mur msq
-        v.push_back(ar.add(Mc));                                               // valid
+        auto& u = oo[b];
+        for (int k = 0; k < 3; k++) u.push_back(ao.add(Mc * ldn * 8));          // Vf Rf Cf
+        for (int k = 0; k < 3; k++) u.push_back(ao.add(Mc * 8));                // mu mur msq
+        u.push_back(ao.add(Mc));                                               // valid
+        for (int k = 0; k < 3; k++) u.push_back(ao.add(P.pairs ? n * ldm * 8 : 8));  // Vs Rs Cs
         v.push_back(ar.add((size_t)P.T * ldn * 8));                            // Yc
         v.push_back(ar.add((size_t)P.TP * ldn * 8));                           // Yn
         v.push_back(ar.add((size_t)P.T * 8));                                  // syy
@@ -2680,7 +2682,6 @@ static void layout_problems(discover_ctx* ctx, const discover_problem* probs, in
         v.push_back(ar.add((size_t)P.Tl * P.N * 8));                           // scores
         v.push_back(ar.add((size_t)P.fix_cap * 8));                            // fix_ids
         v.push_back(ar.add(sp.stream3 ? (size_t)P.fix_cap * 8 : 8));           // fix_ids3
-        for (int k = 0; k < 3; k++) v.push_back(ar.add(P.pairs ? n * ldm * 8 : 8));  // Vs Rs Cs
         const size_t L2 = sp.stream3 ? (size_t)sp.d.L[2] : 1;
         v.push_back(ar.add(L2));                                               // r2v
         v.push_back(ar.add(L2 * 8));                                           // r2m
@@ -2689,6 +2690,7 @@ static void layout_problems(discover_ctx* ctx, const discover_problem* probs, in
         v.push_back(ar.add(prm.precision != DISCOVER_FP64 ? (size_t)16 * P.ldl * 2 : 8));  // Ylp
     }
     char* base = (char*)ctx->raw("scr_arena", ar.total);
+    char* obase = (char*)ctx->raw("scr_ops" + ctx->ops_tag, ao.total);
     // counters stay apart from the shared arena: a captured run checks the
     // bad-target flags after later calls have reused the arena
     unsigned long long* ctr = ctx->buf<unsigned long long>("scr_ctr" + ctx->tag, 4 * (size_t)nb);
@@ -2696,15 +2698,17 @@ static void layout_problems(discover_ctx* ctx, const discover_problem* probs, in
     for (int b = 0; b < nb; b++) {
         Problem& P = PS[b];
         const auto& v = o[b];
-        int q = 0;
+        const auto& u = oo[b];
+        int q = 0, qo = 0;
         auto at = [&](void) { return base + v[q++]; };
-        P.Vf = (double*)at(); P.Rf = (double*)at(); P.Cf = (double*)at();
-        P.mu = (double*)at(); P.mur = (double*)at(); P.msq = (double*)at();
-        P.valid = (uint8_t*)at();
+        auto ato = [&](void) { return obase + u[qo++]; };
+        P.Vf = (double*)ato(); P.Rf = (double*)ato(); P.Cf = (double*)ato();
+        P.mu = (double*)ato(); P.mur = (double*)ato(); P.msq = (double*)ato();
+        P.valid = (uint8_t*)ato();
+        P.Vs = (double*)ato(); P.Rs = (double*)ato(); P.Cs = (double*)ato();
         P.Yc = (double*)at(); P.Yn = (double*)at(); P.syy = (double*)at(); P.ysum = (double*)at();
         P.scores = (double*)at();
         P.fix_ids = (int64_t*)at(); P.fix_ids3 = (int64_t*)at();
-        P.Vs = (double*)at(); P.Rs = (double*)at(); P.Cs = (double*)at();
         uint8_t* r2v = (uint8_t*)at();
         double* r2m = (double*)at();
         double* r2q = (double*)at();
@@ -2814,8 +2818,21 @@ static void screen_all(discover_ctx* ctx, const discover_problem* probs, int nb,
         nmax = std::max(nmax, P.n);
         for (int r = 0; r < a.nlev; r++) wmax[r] = std::max(wmax[r], a.rs[r + 1] - a.rs[r]);
     }
+    // the operands of these problems are already in place (same arena, same
+    // layout, same X) when an earlier screen of the sequence made them
+    std::vector<int64_t> sig;
+    for (int b = 0; b < nb; b++) {
+        const Problem& P = PS[b];
+        sig.insert(sig.end(), {(int64_t)(uintptr_t)probs[b].X, probs[b].ldx, (int64_t)P.n, (int64_t)P.Mc,
+                               (int64_t)P.ldn, (int64_t)P.ldm, (int64_t)P.pairs,
+                               (int64_t)(uintptr_t)P.Vf, (int64_t)(uintptr_t)P.Vs});
+        const auto& rs = P.plan->sp.rung_start;
+        sig.insert(sig.end(), rs.begin(), rs.end());
+    }
+    const bool ops_ready = ctx->ops_reuse && sig == ctx->ops_sig;
+    ctx->ops_sig = sig;
     const ctab<MatArgs> dma = ct(ctx->upload("scr_mat", ma, st));
-    {
+    if (!ops_ready) {
         KTimer kt(ctx, st, "materialise");
         for (int r = 0; r < nlev; r++) {
             if (!wmax[r]) continue;
@@ -2857,7 +2874,7 @@ static void screen_all(discover_ctx* ctx, const discover_problem* probs, int nb,
         tn = std::max(tn, P.n);
         tm = std::max(tm, P.Mc);
     }
-    if (!tr.empty()) {
+    if (!tr.empty() && !ops_ready) {
         k_transpose<<<dim3((unsigned)cdiv(tn, 32), (unsigned)cdiv(tm, 32), (unsigned)(3 * tr.size())),
                       dim3(32, 8), 0, st>>>(ct(ctx->upload("scr_tr", tr, st)));
         check_launch("k_transpose");
