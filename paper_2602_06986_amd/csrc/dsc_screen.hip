@@ -2052,7 +2052,7 @@ __device__ __forceinline__ void d_groups_lds(
     int64_t* __restrict__ res, int64_t total_flags) {
     __shared__ int64_t part[GRP_THREADS];
     __shared__ __align__(16) int32_t par[GRP_LDS];
-    __shared__ unsigned long long rkey[GRP_LDS];
+    __shared__ __align__(16) unsigned long long rkey[GRP_LDS];   // also the sort array of phase 5
     __shared__ uint32_t blkb[GRP_LDS / 32];
     __shared__ int changed, undecided;
     const int t = threadIdx.x;
@@ -2127,8 +2127,43 @@ __device__ __forceinline__ void d_groups_lds(
     const int64_t merged_tot = part[GRP_THREADS - 1];
     __syncthreads();
     const int64_t ns = min((int64_t)k, nunb);
-    // 5. representatives in (-score, ID) order (rank sort of <= k entries,
-    // staged through LDS in tiles that reuse the parent array)
+    // 5. representatives in (-score, ID) order: up to 1024 by a bitonic
+    // sort with one entry per thread (partners within a wave by register
+    // shuffles, across waves through LDS, the key array's memory), more by
+    // rank counting in tiles that reuse the parent array.  IDs are
+    // distinct, so the order is strict and both give the same result.
+    if (ns <= GRP_THREADS) {
+        int N2 = 1;
+        while (N2 < ns) N2 <<= 1;
+        SK e{-INFINITY, INT64_MAX};                               // padding sorts last
+        if (t < ns) {
+            const unsigned long long kk = rkey[headpos[t]];
+            e = SK{ps[order[(int)(kk & 4095ull)]], (long long)(kk >> 12)};
+        }
+        SK* srt = (SK*)rkey;                                      // 1024 entries = 16 KB
+        for (int kb = 2; kb <= N2; kb <<= 1)
+            for (int j = kb >> 1; j > 0; j >>= 1) {
+                SK o;
+                if (j >= 64) {                                    // partner in another wave
+                    __syncthreads();
+                    srt[t] = e;
+                    __syncthreads();
+                    o = srt[t ^ j];
+                } else {
+                    o.s = __shfl_xor(e.s, j, 64);
+                    o.id = __shfl_xor(e.id, j, 64);
+                }
+                const bool o_first = o.s > e.s || (o.s == e.s && o.id < e.id);
+                // the lower index of a pair keeps the first entry in runs that
+                // ascend (bit kb of the index clear), the later one otherwise
+                const bool keep_first = ((t & j) == 0) == ((t & kb) == 0);
+                if (o_first == keep_first) e = o;
+            }
+        if (t < ns) {
+            out_ids[t] = e.id;
+            out_sc[t] = e.s;
+        }
+    } else {
     SK* tile = (SK*)par;                                          // 1024 entries = 16 KB
     for (int64_t i0 = 0; i0 < ns; i0 += GRP_THREADS) {
         const int64_t i = i0 + t;
@@ -2154,6 +2189,7 @@ __device__ __forceinline__ void d_groups_lds(
             out_ids[rank] = ii;
             out_sc[rank] = si;
         }
+    }
     }
     for (int64_t i = ns + t; i < k; i += GRP_THREADS) {
         out_ids[i] = -1;
