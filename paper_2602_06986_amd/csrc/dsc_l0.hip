@@ -80,9 +80,7 @@ __device__ __forceinline__ void d_l0_prep(int n, int S, const double* __restrict
 typedef double dsc_v4d __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ void d_gram(int M, int ldz, int nk, const double* __restrict__ Z,
-                                       double* __restrict__ G, int ldg) {
-    const int bi = blockIdx.y * 32, bj = blockIdx.x * 32;
-    if (bj < bi) return;                      // lower triangle mirrored below (block-uniform)
+                                       double* __restrict__ G, int ldg, int bi, int bj) {
     __shared__ dsc_v4d part[3][4][64];        // waves 1..3: their 2 x 2 partial tiles
     const int wv = wave_id();
     const int lane = threadIdx.x & 63;
@@ -851,13 +849,32 @@ __global__ __launch_bounds__(256) void k_omp_prep(int n, int S, const double* __
     *nact = c;
 }
 
-// grid (column tiles, row tiles, problems)
+// grid (8 x the tiles of the busiest XCD, 1, problems).  Block p runs on
+// XCD p mod 8; XCD x takes the tile rows x, x + 8, x + 16, ... of the upper
+// triangle and walks its tiles column by column, so its band of Z rows
+// stays in its L2 while each column tile is read once.
 __global__ __launch_bounds__(256) void k_gram(ctab<PrepArgs> A) {
     const PrepArgs& a = tab(A, blockIdx.z);
     DSC_GLOBAL(a.Z); DSC_GLOBAL(a.G);
     const int M = a.S + 1;
-    if ((int)blockIdx.x * 32 >= M || (int)blockIdx.y * 32 >= M) return;
-    d_gram(M, a.ldz, a.ldz, a.Z, a.G, a.ldg);
+    const int gt = (M + 31) / 32;
+    const int x = blockIdx.x & 7, l = blockIdx.x >> 3;
+    int bj = x, cum = 0;
+    for (; bj < gt; bj++) {                   // column bj holds rows x + 8m <= bj
+        const int c = (bj - x) / 8 + 1;
+        if (l < cum + c) break;
+        cum += c;
+    }
+    if (bj >= gt) return;                     // (block-uniform) past this XCD's tiles
+    const int bi = x + 8 * (l - cum);
+    d_gram(M, a.ldz, a.ldz, a.Z, a.G, a.ldg, 32 * bi, 32 * bj);
+}
+
+// Blocks per XCD of the Gram launch for gt tile rows (XCD 0 has the most).
+static int gram_xcd_tiles(int gt) {
+    int c = 0;
+    for (int bj = 0; bj < gt; bj++) c += bj / 8 + 1;
+    return c;
 }
 
 // grid (a blocks, b rows, problems)
@@ -1211,8 +1228,8 @@ void l0_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D
     {
         KTimer kt(ctx, st, "l0_gram");
         k_l0_prep<<<dim3((unsigned)cdiv(Smax + 1, 4), nb), 256, 0, st>>>(dpa);
-        const unsigned gt = (unsigned)cdiv(Smax + 1, 32);
-        k_gram<<<dim3(gt, gt, nb), 256, 0, st>>>(dpa);
+        const int gt = (int)cdiv(Smax + 1, 32);
+        k_gram<<<dim3(8u * (unsigned)gram_xcd_tiles(gt), 1, nb), 256, 0, st>>>(dpa);
         check_launch("k_gram");
     }
     if (D == 3) {
