@@ -32,9 +32,9 @@ L0_FLOP_PER_SUBSET = 10      # Schur rank-1 extension per 3-subset (see DESIGN.m
 # plain 1 GiB device copy.  Valid only for the kernel source they were taken on.
 SWEEP3_COUNTERS = {
     "source": "paper_2602_06986_amd/csrc/dsc_l0.hip",
-    "sha256": "1f536abef1344594908ce418bfae9d1792ccea5c8777d0b4b1457cf3e205ee1d",
-    "fetch_kib": 250144.5, "fetch_scale": 1.9999,
-    "write_kib": 14724.8, "write_scale": 1.0,
+    "sha256": "f52bc97998b6e3c859188c9caa521e644dc0202b347570f0cca69bd6e0838007",
+    "fetch_kib": 250087.5, "fetch_scale": 1.9999,
+    "write_kib": 14775.9, "write_scale": 1.0,
 }
 
 
