@@ -217,3 +217,29 @@ def test_sisso_graph_omp_and_graph_timers(torch, ctx, D):
     finally:
         ctx.set_timing(False)
         ctx.set_graph_timing([])
+
+
+def test_sisso_sequence_several_residuals(torch, ctx, D):
+    """discover_sisso_batch with three residuals: dimensions 2 and 3 screen
+    three targets (maximum score) over the operand features that dimension 1
+    made, and the eager call and its graph replay give exactly the Python
+    loop's selections and models."""
+    rng = np.random.default_rng(123)
+    p, n = 6, 230
+    X = rng.uniform(0.5, 2.0, size=(p, n))
+    y = 0.7 - 1.2 * X[0] * X[2] + 0.6 * X[1] / X[3] + 0.3 * np.log(X[4]) + 0.01 * rng.normal(size=n)
+    Xd, yd = dev(torch, X), dev(torch, y)
+    prm = D.params(rung=2, k=18)
+    Dd, m = 3, 3
+    ref = ctx.sisso(Xd, yd, prm, Dd, n_resid=m)
+    for call in range(2):
+        ids, sc, sub, rmse, coef, replayed = ctx.sisso_batch_graph([Xd], [yd], prm, Dd, m=m)
+        assert replayed == (1 if call > 0 else 0), (call, replayed, getattr(ctx, "capture_error", ""))
+        for d in range(Dd):
+            rd = ref["dims"][d]
+            assert np.array_equal(ids[0, d].cpu().numpy(), rd["sel_ids"].cpu().numpy()), (call, d)
+            assert np.array_equal(_bits(sc[0, d]), _bits(rd["sel_scores"])), (call, d)
+            for q in range(m):
+                assert np.array_equal(sub[0, d, q, :d + 1].cpu().numpy(), rd["subsets"][q].cpu().numpy()), (call, d, q)
+                assert np.array_equal(_bits(rmse[0, d, q:q + 1]), _bits(rd["rmse"][q:q + 1])), (call, d, q)
+                assert np.array_equal(_bits(coef[0, d, q, :d + 2]), _bits(rd["coef"][q])), (call, d, q)

@@ -152,11 +152,14 @@ def test_multitarget_per_target(torch, ctx, D, oracle_mod):
 
 
 # seeds 7 and 8: k large enough that the pool exceeds 4096 entries (the
-# duplicate groups are then formed in global memory instead of LDS)
+# duplicate groups are then formed in global memory instead of LDS); seed 9:
+# more than 1024 representatives from a pool within 4096 entries (the LDS
+# group kernel orders them by rank counts instead of its bitonic sort)
 @pytest.mark.parametrize("seed,p,n,B,R,dedup,k", [
     (0, 5, 37, 0, 2, True, 7), (1, 7, 129, 2, 2, True, 40), (2, 4, 64, 0, 2, False, 25),
     (3, 6, 65, 3, 2, True, 300), (4, 3, 20, 1, 1, True, 50), (5, 9, 200, 0, 1, True, 10),
-    (6, 5, 3, 0, 1, True, 5), (7, 7, 90, 0, 2, True, 2600), (8, 6, 65, 2, 2, True, 2100)])
+    (6, 5, 3, 0, 1, True, 5), (7, 7, 90, 0, 2, True, 2600), (8, 6, 65, 2, 2, True, 2100),
+    (9, 7, 90, 0, 2, True, 1200)])
 def test_screen_random(torch, ctx, D, oracle_mod, seed, p, n, B, R, dedup, k):
     """Ragged sizes (n and operand counts off the 64 grid), units on/off,
     duplicates on/off, k beyond the number of valid candidates."""
