@@ -936,6 +936,8 @@ __global__ __launch_bounds__(256) void k_band_offsets(ctab<RefitArgs> A, int na,
     }
 }
 
+constexpr int REFIT_LDS_NA = 256;     // problems whose band offsets the refit forms itself
+
 // QR refit of every band entry of every problem: persistent workgroups
 // take entries from the merged list, so one problem with a large band is
 // spread over the whole GPU.
@@ -947,6 +949,22 @@ __global__ __launch_bounds__(256) void k_refit_all(ctab<RefitArgs> A, int na,
     __shared__ double rss;
     extern __shared__ double dsm[];              // sld doubles when use_lds
     double* S = scratch + (int64_t)blockIdx.x * sld;
+    // up to REFIT_LDS_NA problems, every block forms the band offsets itself
+    // (an exclusive sum of the band sizes) instead of a launch of their own
+    __shared__ int64_t lboff[REFIT_LDS_NA + 1];
+    if (na <= REFIT_LDS_NA) {
+        if (threadIdx.x < na) {
+            const RefitArgs& a = tab(A, threadIdx.x);
+            lboff[threadIdx.x + 1] = min((int64_t)*a.bcnt, a.bcap);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            lboff[0] = 0;
+            for (int b = 1; b <= na; b++) lboff[b] += lboff[b - 1];
+        }
+        __syncthreads();
+        boff = lboff;
+    }
     const int64_t total = boff[na];
     for (int64_t e = blockIdx.x; e < total; e += gridDim.x) {
         int lo = 0, hi = na;                     // boff[lo] <= e < boff[hi]
@@ -1375,7 +1393,7 @@ void l0_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D
         }
         {
             KTimer kt(ctx, st, "l0_refit");
-            k_band_offsets<<<1, 256, 0, st>>>(dfa, na, boff);
+            if (na > REFIT_LDS_NA) k_band_offsets<<<1, 256, 0, st>>>(dfa, na, boff);
             const int rl = sld * (int64_t)sizeof(double) <= 65536 ? 1 : 0;   // QR columns in LDS
             k_refit_all<<<NREFIT, 256, rl ? (size_t)sld * sizeof(double) : 0, st>>>(dfa, na, boff, rscratch,
                                                                                    sld, rl);
