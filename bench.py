@@ -32,9 +32,9 @@ L0_FLOP_PER_SUBSET = 10      # Schur rank-1 extension per 3-subset (see DESIGN.m
 # plain 1 GiB device copy.  Valid only for the kernel source they were taken on.
 SWEEP3_COUNTERS = {
     "source": "paper_2602_06986_amd/csrc/dsc_l0.hip",
-    "sha256": "f52bc97998b6e3c859188c9caa521e644dc0202b347570f0cca69bd6e0838007",
-    "fetch_kib": 250087.5, "fetch_scale": 1.9999,
-    "write_kib": 14775.9, "write_scale": 1.0,
+    "sha256": "b9bbd8b1a1e95f7a53130ec613b85aa95609a02006553bb21a4c88753453eeec",
+    "fetch_kib": 249991.8, "fetch_scale": 1.9999,
+    "write_kib": 14776.1, "write_scale": 1.0,
 }
 
 
