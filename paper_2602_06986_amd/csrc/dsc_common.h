@@ -299,6 +299,14 @@ __device__ __forceinline__ double wave_sum(double v) {
     return (lane_f64(v, 0) + lane_f64(v, 16)) + (lane_f64(v, 32) + lane_f64(v, 48));
 }
 
+__device__ __forceinline__ double wave_min(double v) {
+    v = fmin(v, dpp_f64<0xB1>(v));
+    v = fmin(v, dpp_f64<0x4E>(v));
+    v = fmin(v, dpp_f64<0x141>(v));
+    v = fmin(v, dpp_f64<0x140>(v));
+    return fmin(fmin(lane_f64(v, 0), lane_f64(v, 16)), fmin(lane_f64(v, 32), lane_f64(v, 48)));
+}
+
 __device__ __forceinline__ double wave_max(double v) {
     v = fmax(v, dpp_f64<0xB1>(v));
     v = fmax(v, dpp_f64<0x4E>(v));

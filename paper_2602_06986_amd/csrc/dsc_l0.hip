@@ -729,8 +729,24 @@ __device__ __forceinline__ void block_lsq(int n, int d, const int* idx, const do
     }
 }
 
-// Rank the band (one thread): repeatedly take the minimum RSS; entries
-// within TAU_TIE * yy of it are tied and the smallest sorted-ID tuple wins.
+// Rank the band: repeatedly take the minimum RSS; entries within
+// TAU_TIE * yy of it are tied and the smallest sorted-ID tuple wins.  The
+// 256 threads of the block scan the band in parallel: the minimum RSS does
+// not depend on the order of the scan, and band subsets are distinct, so
+// the winning tuple is unique and every order of the scan finds it.
+struct RankKey {
+    int64_t k[3];                 // sorted IDs (unused places 0)
+    int64_t e;                    // band entry, -1 for none
+};
+
+__device__ __forceinline__ bool rank_before(const RankKey& x, const RankKey& y) {
+    if (y.e < 0) return x.e >= 0;
+    if (x.e < 0) return false;
+    for (int j = 0; j < 3; j++)
+        if (x.k[j] != y.k[j]) return x.k[j] < y.k[j];
+    return x.e < y.e;
+}
+
 __device__ __forceinline__ void d_rank_models(const int4* __restrict__ band, const double* __restrict__ brss,
                               const double* __restrict__ bcoef,
                               const unsigned long long* __restrict__ bcnt, int64_t bcap, int D, int m,
@@ -738,50 +754,63 @@ __device__ __forceinline__ void d_rank_models(const int4* __restrict__ band, con
                               int n, uint8_t* __restrict__ taken, int32_t* __restrict__ out_sub,
                               double* __restrict__ out_rmse, double* __restrict__ out_coef,
                               int32_t* __restrict__ chosen, int sub_ld, int coef_ld) {
-    if (threadIdx.x != 0) return;
+    __shared__ double smin[4];
+    __shared__ RankKey skey[4];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const double yy = *yyp;
     const int64_t nb = min((int64_t)*bcnt, bcap);
-    for (int64_t e = 0; e < nb; e++) taken[e] = !(brss[e] >= 0.0);
+    for (int64_t e = t; e < nb; e += 256) taken[e] = !(brss[e] >= 0.0);
+    __syncthreads();
     for (int q = 0; q < m; q++) {
         double rmin = INFINITY;
-        for (int64_t e = 0; e < nb; e++)
-            if (!taken[e] && brss[e] < rmin) rmin = brss[e];
-        int64_t pick = -1;
-        int64_t key[3] = {0, 0, 0}, bk[3] = {0, 0, 0};
+        for (int64_t e = t; e < nb; e += 256)
+            if (!taken[e]) rmin = fmin(rmin, brss[e]);
+        rmin = wave_min(rmin);
+        if (lane == 0) smin[wv] = rmin;
+        __syncthreads();
+        rmin = fmin(fmin(smin[0], smin[1]), fmin(smin[2], smin[3]));
+        RankKey best{{0, 0, 0}, -1};
         if (rmin < INFINITY) {
-            for (int64_t e = 0; e < nb; e++) {
+            for (int64_t e = t; e < nb; e += 256) {
                 if (taken[e] || !(brss[e] <= rmin + TAU_TIE * yy)) continue;
-                const int4 s = band[e];
-                const int pos[3] = {s.x, s.y, s.z};
-                for (int j = 0; j < D; j++) key[j] = ids[pos[j]];
+                const int4 sv = band[e];
+                const int pos[3] = {sv.x, sv.y, sv.z};
+                RankKey c{{0, 0, 0}, e};
+                for (int j = 0; j < D; j++) c.k[j] = ids[pos[j]];
                 for (int u = 1; u < D; u++)          // sort the ID tuple
-                    for (int v = u; v > 0 && key[v - 1] > key[v]; v--) {
-                        const int64_t tt = key[v]; key[v] = key[v - 1]; key[v - 1] = tt;
+                    for (int v = u; v > 0 && c.k[v - 1] > c.k[v]; v--) {
+                        const int64_t tt = c.k[v]; c.k[v] = c.k[v - 1]; c.k[v - 1] = tt;
                     }
-                bool better = pick < 0;
-                for (int j = 0; j < D && !better; j++) {
-                    if (key[j] < bk[j]) { better = true; break; }
-                    if (key[j] > bk[j]) break;
-                }
-                if (better) {
-                    pick = e;
-                    for (int j = 0; j < D; j++) bk[j] = key[j];
-                }
+                if (rank_before(c, best)) best = c;
             }
         }
-        chosen[q] = (int32_t)pick;
-        if (pick < 0) {
-            for (int j = 0; j < D; j++) out_sub[q * sub_ld + j] = -1;
-            out_rmse[q] = __longlong_as_double(0x7FF8000000000000LL);
-            for (int j = 0; j <= D; j++) out_coef[q * coef_ld + j] = __longlong_as_double(0x7FF8000000000000LL);
-            continue;
+        for (int o = 32; o > 0; o >>= 1) {           // wave minimum in the tuple order
+            RankKey x;
+            for (int j = 0; j < 3; j++) x.k[j] = __shfl_xor(best.k[j], o, 64);
+            x.e = __shfl_xor(best.e, o, 64);
+            if (rank_before(x, best)) best = x;
         }
-        taken[pick] = 1;
-        const int4 s = band[pick];
-        const int pos[3] = {s.x, s.y, s.z};
-        for (int j = 0; j < D; j++) out_sub[q * sub_ld + j] = pos[j];
-        out_rmse[q] = sqrt(brss[pick] / n);
-        for (int j = 0; j <= D; j++) out_coef[q * coef_ld + j] = bcoef[pick * (D + 1) + j];
+        if (lane == 0) skey[wv] = best;
+        __syncthreads();
+        if (t == 0) {
+            for (int w = 0; w < 4; w++)
+                if (rank_before(skey[w], best)) best = skey[w];
+            const int64_t pick = best.e;
+            chosen[q] = (int32_t)pick;
+            if (pick < 0) {
+                for (int j = 0; j < D; j++) out_sub[q * sub_ld + j] = -1;
+                out_rmse[q] = __longlong_as_double(0x7FF8000000000000LL);
+                for (int j = 0; j <= D; j++) out_coef[q * coef_ld + j] = __longlong_as_double(0x7FF8000000000000LL);
+            } else {
+                taken[pick] = 1;
+                const int4 sv = band[pick];
+                const int pos[3] = {sv.x, sv.y, sv.z};
+                for (int j = 0; j < D; j++) out_sub[q * sub_ld + j] = pos[j];
+                out_rmse[q] = sqrt(brss[pick] / n);
+                for (int j = 0; j <= D; j++) out_coef[q * coef_ld + j] = bcoef[pick * (D + 1) + j];
+            }
+        }
+        __syncthreads();                             // taken and the shared slots are settled
     }
 }
 
