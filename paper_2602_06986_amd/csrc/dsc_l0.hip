@@ -80,7 +80,8 @@ __device__ __forceinline__ void d_l0_prep(int n, int S, const double* __restrict
 typedef double dsc_v4d __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ void d_gram(int M, int ldz, int nk, const double* __restrict__ Z,
-                                       double* __restrict__ G, int ldg, int bi, int bj) {
+                                       double* __restrict__ G, int ldg, int bi, int bj,
+                                       double* __restrict__ dg) {
     __shared__ dsc_v4d part[3][4][64];        // waves 1..3: their 2 x 2 partial tiles
     const int wv = wave_id();
     const int lane = threadIdx.x & 63;
@@ -152,6 +153,7 @@ __device__ __forceinline__ void d_gram(int M, int ldz, int nk, const double* __r
                 if (i < M && j < M && i <= j) {
                     G[(int64_t)i * ldg + j] = t[r];
                     G[(int64_t)j * ldg + i] = t[r];
+                    if (i == j) dg[i] = t[r];
                 }
             }
         }
@@ -165,6 +167,7 @@ __device__ __forceinline__ void d_gram(int M, int ldz, int nk, const double* __r
 // threshold are expanded again.
 struct SweepArgs {
     const double* G;
+    const double* dg;         // G's diagonal, contiguous
     int ldg, S, D;
     const double4* E;         // D = 3: (a, b) factor table, E[b * lde + a]
     int lde;
@@ -273,12 +276,14 @@ struct Sw3Lane {
 // pair (a, b), and every (a, b) that cannot start a triple, carries
 // (0, 0, 0, -inf): h_b = 0 leaves den = d_c, and w = -inf makes q = -inf
 // in every form of the sweep (the bounded test fails, the exact value is
-// +inf in negated form, which the minimum skips).
-__device__ __forceinline__ double4 sw3_b_entry(const double* G, int ldg, int S, const double* Ga,
+// +inf in negated form, which the minimum skips).  ub = G[a][b]; G[b][b]
+// comes from the diagonal copy dg and G[b][y] from row S (G is written
+// mirrored, so both equal the transposed entries bit for bit), so that
+// lanes with consecutive b read consecutive addresses.
+__device__ __forceinline__ double4 sw3_b_entry(const double* G, int ldg, int S, const double* dg, double ub,
                                                double ica, double ca, int b) {
-    const double ub = Ga[b];
-    const double db = G[(int64_t)b * ldg + b] - ub * ub * ica;
-    const double zb = G[(int64_t)b * ldg + S] - ub * ca * ica;
+    const double db = dg[b] - ub * ub * ica;
+    const double zb = G[(int64_t)S * ldg + b] - ub * ca * ica;
     if (db > PIV_TOL) {
         const double hb = 1.0 / db;
         return make_double4(ub, zb * hb, hb, ca * ca * ica + zb * zb * hb);
@@ -286,14 +291,14 @@ __device__ __forceinline__ double4 sw3_b_entry(const double* G, int ldg, int S, 
     return make_double4(0.0, 0.0, 0.0, -__builtin_inf());
 }
 
-__device__ __forceinline__ Sw3Lane sw3_lane(const double* G, int ldg, int S, const double* Ga,
+__device__ __forceinline__ Sw3Lane sw3_lane(const double* G, int ldg, int S, const double* dg, const double* Ga,
                                             double caa, double ca, int c, bool cok) {
     Sw3Lane L;
     const double uc = Ga[c];
     L.upc = uc * (1.0 / caa);
     // an out-of-range c gets a negative d_c, so none of its triples passes
-    L.dc = cok ? G[(int64_t)c * ldg + c] - uc * L.upc : -1.0;
-    L.zc = G[(int64_t)c * ldg + S] - ca * L.upc;
+    L.dc = cok ? dg[c] - uc * L.upc : -1.0;
+    L.zc = G[(int64_t)S * ldg + c] - ca * L.upc;
     return L;
 }
 
@@ -310,16 +315,16 @@ __device__ __forceinline__ double sw3_q(const double4& e, const Sw3Lane& L, doub
 // a < b and the entries a = b .. b + 15 that a block starting below b may
 // also read (a wave's a values reach at most 15 past the block's first a).
 __device__ __forceinline__ void d_sw3_table(const double* __restrict__ G, int ldg, int S,
+                                            const double* __restrict__ dg,
                                             double4* __restrict__ E, int lde, double th) {
     const int b = blockIdx.y;
     const int a = blockIdx.x * 256 + threadIdx.x;
     if (a >= lde || a > b + 15) return;
     double4 e = make_double4(0.0, 0.0, 0.0, -__builtin_inf());
     if (a < S - 2 && b > a) {
-        const double* Ga = G + (int64_t)a * ldg;
-        const double caa = Ga[a];
+        const double caa = dg[a];                       // lanes take consecutive a: row reads
         if (caa > PIV_TOL) {
-            e = sw3_b_entry(G, ldg, S, Ga, 1.0 / caa, Ga[S], b);
+            e = sw3_b_entry(G, ldg, S, dg, G[(int64_t)b * ldg + a], 1.0 / caa, G[(int64_t)S * ldg + a], b);
             e.w -= th;
         }
     }
@@ -403,7 +408,7 @@ __device__ __forceinline__ void sw3_run(const double4* __restrict__ Ew, int lde,
 template <bool BOUND>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_sweep3(ctab<SweepArgs> A, const int* __restrict__ bprob) {
     const SweepArgs& g = tab(A, bprob[blockIdx.x]);
-    DSC_GLOBAL(g.G); DSC_GLOBAL(g.E); DSC_GLOBAL(g.items3); DSC_GLOBAL(g.lane_q); DSC_GLOBAL(g.theta);
+    DSC_GLOBAL(g.G); DSC_GLOBAL(g.dg); DSC_GLOBAL(g.E); DSC_GLOBAL(g.items3); DSC_GLOBAL(g.lane_q); DSC_GLOBAL(g.theta);
     const int64_t li = (int64_t)blockIdx.x - g.item0;   // block within its problem
     const int4 item = g.items3[li];
     const int a0 = item.x, c0 = item.y;                  // block: a0..a0+15, c0..c0+63, b in [z, w)
@@ -429,7 +434,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
     for (int k = 0; k < SW3_A; k++) {
         const int ac = min(aw + k, g.S - 1);
         const double* Ga = g.G + (int64_t)ac * g.ldg;
-        L[k] = sw3_lane(g.G, g.ldg, g.S, Ga, Ga[ac], Ga[g.S], cc, true);
+        L[k] = sw3_lane(g.G, g.ldg, g.S, g.dg, Ga, Ga[ac], Ga[g.S], cc, true);
         low[k] = 1.0;
     }
     const double4* Ew = g.E + aw;
@@ -474,6 +479,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
 // -1.  Distinct rows give subsets in distinct sweep lanes (a, c).
 struct ThetaArgs {
     const double* G;
+    const double* dg;         // G's diagonal, contiguous
     int ldg, S;
     double* rowq;
     double* theta;
@@ -492,7 +498,7 @@ __device__ __forceinline__ void wave_argmax(double& v, int& i) {
 // grid (row blocks of 4, problems)
 __global__ __launch_bounds__(256) void k_sw3_rows(ctab<ThetaArgs> A) {
     const ThetaArgs& g = tab(A, blockIdx.y);
-    DSC_GLOBAL(g.G); DSC_GLOBAL(g.rowq);
+    DSC_GLOBAL(g.G); DSC_GLOBAL(g.dg); DSC_GLOBAL(g.rowq);
     const int a = blockIdx.x * 4 + wave_id();
     const int lane = threadIdx.x & 63;
     if (a >= g.S) return;
@@ -504,16 +510,16 @@ __global__ __launch_bounds__(256) void k_sw3_rows(ctab<ThetaArgs> A) {
         double qb = -1.0;
         int bb = 0x7fffffff;
         for (int b = a + 1 + lane; b < g.S - 1; b += 64) {
-            const double4 e = sw3_b_entry(g.G, g.ldg, g.S, Ga, ica, ca, b);
+            const double4 e = sw3_b_entry(g.G, g.ldg, g.S, g.dg, Ga[b], ica, ca, b);
             if (e.w > qb) { qb = e.w; bb = b; }
         }
         wave_argmax(qb, bb);
         if (qb >= 0.0) {
             const int b = bb;
-            const double4 e = sw3_b_entry(g.G, g.ldg, g.S, Ga, ica, ca, b);
+            const double4 e = sw3_b_entry(g.G, g.ldg, g.S, g.dg, Ga[b], ica, ca, b);
             const double* Gb = g.G + (int64_t)b * g.ldg;
             for (int c = b + 1 + lane; c < g.S; c += 64) {
-                const Sw3Lane L = sw3_lane(g.G, g.ldg, g.S, Ga, caa, ca, c, true);
+                const Sw3Lane L = sw3_lane(g.G, g.ldg, g.S, g.dg, Ga, caa, ca, c, true);
                 const double Cp = fma(-e.x, L.upc, Gb[c]);
                 const double ee = fma(-Cp, e.y, L.zc);
                 const double den = fma(-Cp, Cp * e.z, L.dc);
@@ -563,6 +569,7 @@ __global__ __launch_bounds__(256) void k_sw3_theta(ctab<ThetaArgs> A, int m) {
 // Band expansion.  thr = (m-th best lane value) * (1 - 1e-12) - GRAM_DELTA.
 struct BandArgs {
     const double* G;
+    const double* dg;         // G's diagonal, contiguous
     int ldg, S, D;
     const double4* E;         // D = 3 factor table (as in SweepArgs)
     int lde;
@@ -632,7 +639,7 @@ __global__ __launch_bounds__(256) void k_band_lanes(ctab<BandArgs> A) {
 // D = 3: one wave per listed (a, c) lane; its lanes split the b range.
 __global__ __launch_bounds__(256) void k_band_expand3(ctab<BandArgs> A) {
     const BandArgs& g = tab(A, blockIdx.y);
-    DSC_GLOBAL(g.G); DSC_GLOBAL(g.E); DSC_GLOBAL(g.sel); DSC_GLOBAL(g.st); DSC_GLOBAL(g.band); DSC_GLOBAL(g.bcnt); DSC_GLOBAL(g.pairs); DSC_GLOBAL(g.pcnt); DSC_GLOBAL(g.theta);
+    DSC_GLOBAL(g.G); DSC_GLOBAL(g.dg); DSC_GLOBAL(g.E); DSC_GLOBAL(g.sel); DSC_GLOBAL(g.st); DSC_GLOBAL(g.band); DSC_GLOBAL(g.bcnt); DSC_GLOBAL(g.pairs); DSC_GLOBAL(g.pcnt); DSC_GLOBAL(g.theta);
     const double thr = band_thr(g);
     const double th = *g.theta;
     const int64_t np = min((int64_t)*g.pcnt, g.pcap);
@@ -642,7 +649,7 @@ __global__ __launch_bounds__(256) void k_band_expand3(ctab<BandArgs> A) {
         const int blo = max(a + 1, g.pairs[i].z), bhi = min(c, g.pairs[i].w);
         const double* Ga = g.G + (int64_t)a * g.ldg;
         const double caa = Ga[a], ca = Ga[g.S];
-        const Sw3Lane L = sw3_lane(g.G, g.ldg, g.S, Ga, caa, ca, c, true);   // as in the sweep
+        const Sw3Lane L = sw3_lane(g.G, g.ldg, g.S, g.dg, Ga, caa, ca, c, true);   // as in the sweep
         for (int b = blo + lane; b < bhi; b += 64) {
             double4 e = g.E[(int64_t)b * g.lde + a];
             e.w += th;
@@ -841,6 +848,7 @@ struct PrepArgs {
     int64_t ldf;
     const double* y;
     double *Z, *G, *yy;
+    double* dg;               // G's diagonal, contiguous (written by the Gram kernel)
     double4* E;               // D = 3 factor table
     int lde;
     const double* theta;      // D = 3: shift th of the table's Q_ab
@@ -884,7 +892,7 @@ __global__ __launch_bounds__(256) void k_omp_prep(int n, int S, const double* __
 // stays in its L2 while each column tile is read once.
 __global__ __launch_bounds__(256) void k_gram(ctab<PrepArgs> A) {
     const PrepArgs& a = tab(A, blockIdx.z);
-    DSC_GLOBAL(a.Z); DSC_GLOBAL(a.G);
+    DSC_GLOBAL(a.Z); DSC_GLOBAL(a.G); DSC_GLOBAL(a.dg);
     const int M = a.S + 1;
     const int gt = (M + 31) / 32;
     const int x = blockIdx.x & 7, l = blockIdx.x >> 3;
@@ -896,7 +904,7 @@ __global__ __launch_bounds__(256) void k_gram(ctab<PrepArgs> A) {
     }
     if (bj >= gt) return;                     // (block-uniform) past this XCD's tiles
     const int bi = x + 8 * (l - cum);
-    d_gram(M, a.ldz, a.ldz, a.Z, a.G, a.ldg, 32 * bi, 32 * bj);
+    d_gram(M, a.ldz, a.ldz, a.Z, a.G, a.ldg, 32 * bi, 32 * bj, a.dg);
 }
 
 // Blocks per XCD of the Gram launch for gt tile rows (XCD 0 has the most).
@@ -909,9 +917,9 @@ static int gram_xcd_tiles(int gt) {
 // grid (a blocks, b rows, problems)
 __global__ __launch_bounds__(256) void k_sw3_table(ctab<PrepArgs> A) {
     const PrepArgs& a = tab(A, blockIdx.z);
-    DSC_GLOBAL(a.G); DSC_GLOBAL(a.E); DSC_GLOBAL(a.theta);
+    DSC_GLOBAL(a.G); DSC_GLOBAL(a.dg); DSC_GLOBAL(a.E); DSC_GLOBAL(a.theta);
     if ((int)blockIdx.y >= a.S || (int)blockIdx.x * 256 >= a.lde) return;
-    d_sw3_table(a.G, a.ldg, a.S, a.E, a.lde, *a.theta);
+    d_sw3_table(a.G, a.ldg, a.S, a.dg, a.E, a.lde, *a.theta);
 }
 
 struct RefitArgs {
@@ -1257,6 +1265,7 @@ void l0_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D
         v.push_back(ar.add(8));                                            // th
         v.push_back(ar.add(D == 3 ? (size_t)pb.S * 8 : 8));                // row values
         v.push_back(ar.add(8));                                            // lane-list count
+        v.push_back(ar.add((size_t)(pb.S + 1) * 8));                       // G's diagonal
         Smax = std::max(Smax, pb.S);
         ldemax = std::max(ldemax, a.lde);
         if (D == 3) tot_items3 += ni[b]; else tot_items += ni[b];
@@ -1268,6 +1277,7 @@ void l0_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D
         pa[b].yy = (double*)(base + o[b][2]);
         pa[b].E = (double4*)(base + o[b][3]);
         pa[b].theta = (const double*)(base + o[b][4]);
+        pa[b].dg = (double*)(base + o[b][7]);
     }
     const ctab<PrepArgs> dpa = ct(ctx->upload("l0_prep", pa, st));
     const bool bound = D == 3 && m <= SW3_MMAX;
@@ -1284,7 +1294,7 @@ void l0_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D
         if (bound) {                            // the lower bound th of each problem
             std::vector<ThetaArgs> ta(nb);
             for (int b = 0; b < nb; b++)
-                ta[b] = ThetaArgs{pa[b].G, pa[b].ldg, probs[b].S, (double*)(base + o[b][5]),
+                ta[b] = ThetaArgs{pa[b].G, pa[b].dg, pa[b].ldg, probs[b].S, (double*)(base + o[b][5]),
                                   (double*)(base + o[b][4]), (unsigned long long*)(base + o[b][6])};
             const ctab<ThetaArgs> dta = ct(ctx->upload("l0_theta", ta, st));
             k_sw3_rows<<<dim3((unsigned)cdiv(Smax, 4), nb), 256, 0, st>>>(dta);
@@ -1318,7 +1328,7 @@ void l0_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D
     for (int b = 0; b < nb; b++) {
         SweepArgs& g = sa[b];
         g = SweepArgs{};
-        g.G = pa[b].G; g.ldg = pa[b].ldg; g.S = probs[b].S; g.D = D; g.E = pa[b].E; g.lde = pa[b].lde;
+        g.G = pa[b].G; g.dg = pa[b].dg; g.ldg = pa[b].ldg; g.S = probs[b].S; g.D = D; g.E = pa[b].E; g.lde = pa[b].lde;
         g.items = d_items ? d_items + item_off[b] : nullptr;
         g.items3 = d_items3 ? d_items3 + item_off[b] : nullptr;
         g.n_items = ni[b];
@@ -1380,7 +1390,7 @@ void l0_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D
             char* misc = bb + v[6];
             BandArgs& g = ba[q];
             g = BandArgs{};
-            g.G = pa[b].G; g.ldg = pa[b].ldg; g.S = probs[b].S; g.D = D; g.E = pa[b].E; g.lde = pa[b].lde;
+            g.G = pa[b].G; g.dg = pa[b].dg; g.ldg = pa[b].ldg; g.S = probs[b].S; g.D = D; g.E = pa[b].E; g.lde = pa[b].lde;
             g.items = sa[b].items; g.items3 = sa[b].items3;
             g.n_lanes = ni[b] * per;
             g.lane_q = sa[b].lane_q;
