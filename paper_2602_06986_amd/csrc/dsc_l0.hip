@@ -495,13 +495,17 @@ __device__ __forceinline__ void wave_argmax(double& v, int& i) {
     }
 }
 
-// grid (row blocks of 4, problems)
+// grid (rows, problems): the block's 256 threads share the row's b and c
+// ranges; the arg-max (ties to the smaller b) and the maximum do not depend
+// on how the range is split.
 __global__ __launch_bounds__(256) void k_sw3_rows(ctab<ThetaArgs> A) {
     const ThetaArgs& g = tab(A, blockIdx.y);
     DSC_GLOBAL(g.G); DSC_GLOBAL(g.dg); DSC_GLOBAL(g.rowq);
-    const int a = blockIdx.x * 4 + wave_id();
-    const int lane = threadIdx.x & 63;
-    if (a >= g.S) return;
+    __shared__ double sv[4];
+    __shared__ int si[4];
+    const int a = blockIdx.x;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    if (a >= g.S) return;                               // (block-uniform)
     const double* Ga = g.G + (int64_t)a * g.ldg;
     const double caa = Ga[a], ca = Ga[g.S];
     double best = -1.0;
@@ -509,27 +513,34 @@ __global__ __launch_bounds__(256) void k_sw3_rows(ctab<ThetaArgs> A) {
         const double ica = 1.0 / caa;
         double qb = -1.0;
         int bb = 0x7fffffff;
-        for (int b = a + 1 + lane; b < g.S - 1; b += 64) {
+        for (int b = a + 1 + t; b < g.S - 1; b += 256) {
             const double4 e = sw3_b_entry(g.G, g.ldg, g.S, g.dg, Ga[b], ica, ca, b);
             if (e.w > qb) { qb = e.w; bb = b; }
         }
         wave_argmax(qb, bb);
+        if (lane == 0) { sv[wv] = qb; si[wv] = bb; }
+        __syncthreads();
+        for (int w = 0; w < 4; w++)
+            if (sv[w] > qb || (sv[w] == qb && si[w] < bb)) { qb = sv[w]; bb = si[w]; }
+        __syncthreads();                                // sv/si are read before their reuse
         if (qb >= 0.0) {
             const int b = bb;
             const double4 e = sw3_b_entry(g.G, g.ldg, g.S, g.dg, Ga[b], ica, ca, b);
             const double* Gb = g.G + (int64_t)b * g.ldg;
-            for (int c = b + 1 + lane; c < g.S; c += 64) {
+            for (int c = b + 1 + t; c < g.S; c += 256) {
                 const Sw3Lane L = sw3_lane(g.G, g.ldg, g.S, g.dg, Ga, caa, ca, c, true);
                 const double Cp = fma(-e.x, L.upc, Gb[c]);
                 const double ee = fma(-Cp, e.y, L.zc);
                 const double den = fma(-Cp, Cp * e.z, L.dc);
                 if (den > PIV_TOL) best = fmax(best, -sw3_negq(ee * ee, den, e.w, 0.0));
             }
-            int dummy = 0;
-            wave_argmax(best, dummy);
+            best = wave_max(best);
+            if (lane == 0) sv[wv] = best;
+            __syncthreads();
+            best = fmax(fmax(sv[0], sv[1]), fmax(sv[2], sv[3]));
         }
     }
-    if (lane == 0) g.rowq[a] = best;
+    if (t == 0) g.rowq[a] = best;
 }
 
 // Step 2, one block per problem: theta = the m-th largest row value (m
@@ -1297,7 +1308,7 @@ void l0_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D
                 ta[b] = ThetaArgs{pa[b].G, pa[b].dg, pa[b].ldg, probs[b].S, (double*)(base + o[b][5]),
                                   (double*)(base + o[b][4]), (unsigned long long*)(base + o[b][6])};
             const ctab<ThetaArgs> dta = ct(ctx->upload("l0_theta", ta, st));
-            k_sw3_rows<<<dim3((unsigned)cdiv(Smax, 4), nb), 256, 0, st>>>(dta);
+            k_sw3_rows<<<dim3((unsigned)Smax, nb), 256, 0, st>>>(dta);
             k_sw3_theta<<<nb, 256, 0, st>>>(dta, m);
         } else {                                // unbounded: th = 0
             std::vector<FillSeg> fz;
