@@ -32,9 +32,9 @@ L0_FLOP_PER_SUBSET = 10      # Schur rank-1 extension per 3-subset (see DESIGN.m
 # plain 1 GiB device copy.  Valid only for the kernel source they were taken on.
 SWEEP3_COUNTERS = {
     "source": "paper_2602_06986_amd/csrc/dsc_l0.hip",
-    "sha256": "b9bbd8b1a1e95f7a53130ec613b85aa95609a02006553bb21a4c88753453eeec",
-    "fetch_kib": 249991.8, "fetch_scale": 1.9999,
-    "write_kib": 14776.1, "write_scale": 1.0,
+    "sha256": "c1b0a3aad4754614d12925bb6408b336f57f9b63b93acc5910aebaf1201c81ab",
+    "fetch_kib": 250171.5, "fetch_scale": 1.9999,
+    "write_kib": 14776.0, "write_scale": 1.0,
 }
 
 
