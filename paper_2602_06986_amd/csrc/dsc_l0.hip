@@ -765,6 +765,52 @@ __device__ __forceinline__ bool rank_before(const RankKey& x, const RankKey& y) 
     return x.e < y.e;
 }
 
+// The same ranking by one thread, for short bands (fewer barriers).
+constexpr int64_t RANK_SERIAL = 512;
+
+__device__ __forceinline__ void rank_models_serial(const int4* __restrict__ band, const double* __restrict__ brss,
+                              const double* __restrict__ bcoef, int64_t nb, int D, int m,
+                              const int64_t* __restrict__ ids, double yy, int n, uint8_t* __restrict__ taken,
+                              int32_t* __restrict__ out_sub, double* __restrict__ out_rmse,
+                              double* __restrict__ out_coef, int32_t* __restrict__ chosen, int sub_ld,
+                              int coef_ld) {
+    for (int64_t e = 0; e < nb; e++) taken[e] = !(brss[e] >= 0.0);
+    for (int q = 0; q < m; q++) {
+        double rmin = INFINITY;
+        for (int64_t e = 0; e < nb; e++)
+            if (!taken[e] && brss[e] < rmin) rmin = brss[e];
+        RankKey best{{0, 0, 0}, -1};
+        if (rmin < INFINITY) {
+            for (int64_t e = 0; e < nb; e++) {
+                if (taken[e] || !(brss[e] <= rmin + TAU_TIE * yy)) continue;
+                const int4 sv = band[e];
+                const int pos[3] = {sv.x, sv.y, sv.z};
+                RankKey c{{0, 0, 0}, e};
+                for (int j = 0; j < D; j++) c.k[j] = ids[pos[j]];
+                for (int u = 1; u < D; u++)
+                    for (int v = u; v > 0 && c.k[v - 1] > c.k[v]; v--) {
+                        const int64_t tt = c.k[v]; c.k[v] = c.k[v - 1]; c.k[v - 1] = tt;
+                    }
+                if (rank_before(c, best)) best = c;
+            }
+        }
+        const int64_t pick = best.e;
+        chosen[q] = (int32_t)pick;
+        if (pick < 0) {
+            for (int j = 0; j < D; j++) out_sub[q * sub_ld + j] = -1;
+            out_rmse[q] = __longlong_as_double(0x7FF8000000000000LL);
+            for (int j = 0; j <= D; j++) out_coef[q * coef_ld + j] = __longlong_as_double(0x7FF8000000000000LL);
+            continue;
+        }
+        taken[pick] = 1;
+        const int4 sv = band[pick];
+        const int pos[3] = {sv.x, sv.y, sv.z};
+        for (int j = 0; j < D; j++) out_sub[q * sub_ld + j] = pos[j];
+        out_rmse[q] = sqrt(brss[pick] / n);
+        for (int j = 0; j <= D; j++) out_coef[q * coef_ld + j] = bcoef[pick * (D + 1) + j];
+    }
+}
+
 __device__ __forceinline__ void d_rank_models(const int4* __restrict__ band, const double* __restrict__ brss,
                               const double* __restrict__ bcoef,
                               const unsigned long long* __restrict__ bcnt, int64_t bcap, int D, int m,
@@ -777,6 +823,12 @@ __device__ __forceinline__ void d_rank_models(const int4* __restrict__ band, con
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const double yy = *yyp;
     const int64_t nb = min((int64_t)*bcnt, bcap);
+    if (nb <= RANK_SERIAL) {                         // (block-uniform) a short band: one thread
+        if (t == 0) rank_models_serial(band, brss, bcoef, nb, D, m, ids, yy, n, taken, out_sub, out_rmse,
+                                       out_coef, chosen, sub_ld, coef_ld);
+        __syncthreads();
+        return;
+    }
     for (int64_t e = t; e < nb; e += 256) taken[e] = !(brss[e] >= 0.0);
     __syncthreads();
     for (int q = 0; q < m; q++) {
@@ -802,11 +854,18 @@ __device__ __forceinline__ void d_rank_models(const int4* __restrict__ band, con
                 if (rank_before(c, best)) best = c;
             }
         }
-        for (int o = 32; o > 0; o >>= 1) {           // wave minimum in the tuple order
-            RankKey x;
-            for (int j = 0; j < 3; j++) x.k[j] = __shfl_xor(best.k[j], o, 64);
-            x.e = __shfl_xor(best.e, o, 64);
-            if (rank_before(x, best)) best = x;
+        const uint64_t has = __builtin_amdgcn_ballot_w64(best.e >= 0);
+        if (__popcll(has) > 1) {
+            for (int o = 32; o > 0; o >>= 1) {       // wave minimum in the tuple order
+                RankKey x;
+                for (int j = 0; j < 3; j++) x.k[j] = __shfl_xor(best.k[j], o, 64);
+                x.e = __shfl_xor(best.e, o, 64);
+                if (rank_before(x, best)) best = x;
+            }
+        } else if (has) {                            // one lane holds the wave's only candidate
+            const int src = __builtin_ctzll(has);
+            for (int j = 0; j < 3; j++) best.k[j] = __shfl(best.k[j], src, 64);
+            best.e = __shfl(best.e, src, 64);
         }
         if (lane == 0) skey[wv] = best;
         __syncthreads();
