@@ -672,67 +672,88 @@ __global__ __launch_bounds__(256) void k_band_expand3(ctab<BandArgs> A) {
 }
 
 // ------------------------------------------------------------ QR refit
-// Least squares of y on [1, F rows idx[0..d-1]] by Householder QR, one
-// 256-thread workgroup, matrix in a global scratch slab of (d+2) columns.
-__device__ double block_sum256(double v, double* red) {
-    v = wave_sum(v);
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-    __syncthreads();
-    return (red[0] + red[1]) + (red[2] + red[3]);
-}
-
-// A may be LDS (dynamic shared memory) or a global slab: the function is
-// inlined into each caller's two branches, so each copy addresses its own
-// memory directly; the arithmetic is the same in both.
-__device__ __forceinline__ void block_lsq(int n, int d, const int* idx, const double* __restrict__ F, int64_t ldf,
-                          const double* __restrict__ y, double* A, double* coef, double* rss,
-                          double* resid) {
-    __shared__ double red[4];
-    __shared__ double R[DISCOVER_MAX_D + 1][DISCOVER_MAX_D + 2];
-    const int m = d + 1;
-    double* w = A + (int64_t)m * n;
+// Least squares of y on [1, F rows idx[0..d-1]] by Householder QR in one
+// 256-thread workgroup; A holds the M + 1 columns of n (intercept, the d
+// features, the right-hand side), in LDS (dynamic shared memory) or a
+// global slab — the function is inlined into each caller's branches, so
+// each copy addresses its own memory directly.  The column count M = d + 1
+// is fixed at compile time: each Householder step j forms, in one pass,
+// the norm of column j and its raw products with the later columns and the
+// right-hand side (the reflector v differs from column j only in element j,
+// a_jj - alpha, so v . a_c = a_j . a_c + (v_j - a_jj) a_c[j]) and reduces
+// them together; every loop is unrolled, so a step costs one block
+// reduction and one update pass.  (With run-time counts the same scheme
+// was slower than a reduction per column.)
+template <int M>
+__device__ __forceinline__ void block_lsq_t(int n, const int* idx, const double* __restrict__ F, int64_t ldf,
+                                            const double* __restrict__ y, double* A, double* coef,
+                                            double* rss, double* resid) {
+    constexpr int d = M - 1;
+    __shared__ double redm[M + 1][4];
+    __shared__ double R[M][M + 1];
+    double* w = A + (int64_t)M * n;
     for (int i = threadIdx.x; i < n; i += 256) {
         A[i] = 1.0;
+#pragma unroll
         for (int j = 0; j < d; j++) A[(int64_t)(j + 1) * n + i] = F[(int64_t)idx[j] * ldf + i];
         w[i] = y[i];
     }
     __syncthreads();
-    for (int j = 0; j < m; j++) {
-        double* aj = A + (int64_t)j * n;
-        double loc = 0.0;
-        for (int i = j + threadIdx.x; i < n; i += 256) loc += aj[i] * aj[i];
-        const double nrm = sqrt(block_sum256(loc, red));
+#pragma unroll
+    for (int j = 0; j < M; j++) {
+        const double* aj = A + (int64_t)j * n;
+        double sums[M + 1];                           // [0] |a_j|^2, [q] a_j . a_{j+q} (q = M - j: rhs)
+#pragma unroll
+        for (int q = 0; q <= M - j; q++) sums[q] = 0.0;
+        for (int i = j + threadIdx.x; i < n; i += 256) {
+            const double a = aj[i];
+            sums[0] += a * a;
+#pragma unroll
+            for (int q = 1; q <= M - j; q++) sums[q] += a * A[(int64_t)(j + q) * n + i];
+        }
+#pragma unroll
+        for (int q = 0; q <= M - j; q++) sums[q] = wave_sum(sums[q]);
+        if ((threadIdx.x & 63) == 0)
+#pragma unroll
+            for (int q = 0; q <= M - j; q++) redm[q][threadIdx.x >> 6] = sums[q];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q <= M - j; q++) sums[q] = (redm[q][0] + redm[q][1]) + (redm[q][2] + redm[q][3]);
+        const double nrm = sqrt(sums[0]);
         const double ajj = aj[j];
         const double alpha = ajj > 0 ? -nrm : nrm;
         const double v0 = ajj - alpha;
         const double vv = 2.0 * nrm * (nrm + fabs(ajj));   // v^T v
-        __syncthreads();
-        if (threadIdx.x == 0) aj[j] = v0;
-        __syncthreads();
-        for (int c = j + 1; c <= m; c++) {            // column m is the right-hand side
-            double* ac = c < m ? A + (int64_t)c * n : w;
-            double dl = 0.0;
-            for (int i = j + threadIdx.x; i < n; i += 256) dl += aj[i] * ac[i];
-            const double dot = block_sum256(dl, red);
-            const double gm = vv > 0.0 ? 2.0 * dot / vv : 0.0;
-            for (int i = j + threadIdx.x; i < n; i += 256) ac[i] -= gm * aj[i];
-            __syncthreads();
+        double gm[M + 1];
+#pragma unroll
+        for (int q = 1; q <= M - j; q++) {
+            const double dot = fma(v0 - ajj, A[(int64_t)(j + q) * n + j], sums[q]);
+            gm[q] = vv > 0.0 ? 2.0 * dot / vv : 0.0;
         }
+        __syncthreads();                              // a_cj and a_jj read; redm free
+        for (int i = j + threadIdx.x; i < n; i += 256) {
+            const double vi = i == j ? v0 : aj[i];
+#pragma unroll
+            for (int q = 1; q <= M - j; q++) A[(int64_t)(j + q) * n + i] -= gm[q] * vi;
+        }
+        __syncthreads();
         if (threadIdx.x == 0) {
             R[j][j] = alpha;
-            for (int c = j + 1; c < m; c++) R[j][c] = A[(int64_t)c * n + j];
-            R[j][m] = w[j];
+#pragma unroll
+            for (int c = j + 1; c < M; c++) R[j][c] = A[(int64_t)c * n + j];
+            R[j][M] = w[j];
         }
-        __syncthreads();
     }
     double loc = 0.0;
-    for (int i = m + threadIdx.x; i < n; i += 256) loc += w[i] * w[i];
-    const double r2 = block_sum256(loc, red);
+    for (int i = M + threadIdx.x; i < n; i += 256) loc += w[i] * w[i];
+    loc = wave_sum(loc);
+    if ((threadIdx.x & 63) == 0) redm[0][threadIdx.x >> 6] = loc;
+    __syncthreads();
+    const double r2 = (redm[0][0] + redm[0][1]) + (redm[0][2] + redm[0][3]);
     if (threadIdx.x == 0) {
-        for (int j = m - 1; j >= 0; j--) {
-            double acc = R[j][m];
-            for (int c = j + 1; c < m; c++) acc -= R[j][c] * coef[c];
+        for (int j = M - 1; j >= 0; j--) {
+            double acc = R[j][M];
+            for (int c = j + 1; c < M; c++) acc -= R[j][c] * coef[c];
             coef[j] = acc / R[j][j];
         }
         *rss = r2;
@@ -741,9 +762,26 @@ __device__ __forceinline__ void block_lsq(int n, int d, const int* idx, const do
     if (resid) {
         for (int i = threadIdx.x; i < n; i += 256) {
             double p = coef[0];
+#pragma unroll
             for (int j = 0; j < d; j++) p = fma(coef[j + 1], F[(int64_t)idx[j] * ldf + i], p);
             resid[i] = y[i] - p;
         }
+    }
+}
+
+__device__ __forceinline__ void block_lsq(int n, int d, const int* idx, const double* __restrict__ F,
+                                                int64_t ldf, const double* __restrict__ y, double* A,
+                                                double* coef, double* rss, double* resid) {
+    switch (d + 1) {
+    case 1: block_lsq_t<1>(n, idx, F, ldf, y, A, coef, rss, resid); return;
+    case 2: block_lsq_t<2>(n, idx, F, ldf, y, A, coef, rss, resid); return;
+    case 3: block_lsq_t<3>(n, idx, F, ldf, y, A, coef, rss, resid); return;
+    case 4: block_lsq_t<4>(n, idx, F, ldf, y, A, coef, rss, resid); return;
+    case 5: block_lsq_t<5>(n, idx, F, ldf, y, A, coef, rss, resid); return;
+    case 6: block_lsq_t<6>(n, idx, F, ldf, y, A, coef, rss, resid); return;
+    case 7: block_lsq_t<7>(n, idx, F, ldf, y, A, coef, rss, resid); return;
+    case 8: block_lsq_t<8>(n, idx, F, ldf, y, A, coef, rss, resid); return;
+    default: block_lsq_t<9>(n, idx, F, ldf, y, A, coef, rss, resid); return;
     }
 }
 
