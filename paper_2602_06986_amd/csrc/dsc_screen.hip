@@ -1541,22 +1541,33 @@ __device__ __forceinline__ void d_compact(const double* __restrict__ sc, int64_t
     radix_finish(hist, gsel, gst, sel, st);
     const double th = select_threshold(sel, st);
     const double lo = st[1] ? 0.0 : th - 2.0 * margin;
-    // one atomic per wave: lanes take consecutive slots in lane order
+    // one atomic per wave: lanes take consecutive slots in lane order; four
+    // strided rows of 64 scores are loaded before any is tested, so the
+    // loads overlap (the pool's order does not matter: it is sorted later)
     const int lane = threadIdx.x & 63;
     const uint64_t below = (1ull << lane) - 1ull;
-    for (int64_t i0 = (int64_t)blockIdx.x * 256 + (threadIdx.x & ~63); i0 < N;
-         i0 += (int64_t)gridDim.x * 256) {
-        const int64_t i = i0 + lane;
-        const double x = i < N ? sc[i] : 0.0;
-        const bool take = (x > 0.0 && x >= lo) || (x < 0.0 && -x >= lo);
-        const uint64_t m = __builtin_amdgcn_ballot_w64(take);
-        if (!m) continue;                                 // (wave-uniform)
-        unsigned long long base = 0;
-        if (lane == 0) base = atomicAdd(cnt, (unsigned long long)__popcll(m));
-        base = __shfl(base, 0, 64);
-        if (take) {
-            const unsigned long long slot = base + __popcll(m & below);
-            if ((int64_t)slot < cap) pool[slot] = i;
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t i0 = (int64_t)blockIdx.x * 256 + (threadIdx.x & ~63); i0 < N; i0 += 4 * stride) {
+        double xs[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const int64_t i = i0 + q * stride + lane;
+            xs[q] = i < N ? sc[i] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const int64_t i = i0 + q * stride + lane;
+            const double x = xs[q];
+            const bool take = (x > 0.0 && x >= lo) || (x < 0.0 && -x >= lo);
+            const uint64_t m = __builtin_amdgcn_ballot_w64(take);
+            if (!m) continue;                             // (wave-uniform)
+            unsigned long long base = 0;
+            if (lane == 0) base = atomicAdd(cnt, (unsigned long long)__popcll(m));
+            base = __shfl(base, 0, 64);
+            if (take) {
+                const unsigned long long slot = base + __popcll(m & below);
+                if ((int64_t)slot < cap) pool[slot] = i;
+            }
         }
     }
 }

@@ -114,12 +114,20 @@ static __global__ __launch_bounds__(256) void k_hist(ctab<RadixArgs> A, int leve
     __syncthreads();
     const double* __restrict__ sc = a.x;
     const int64_t N = a.Nd ? min((int64_t)*a.Nd, a.N) : a.N;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256) {
-        const double x = sc[i];
-        if (!(x > 0.0)) continue;
-        const uint64_t u = fx_key(x);
-        if (level == 1 && ((u >> 40) & 0xFFF) != p0) continue;
-        atomicAdd(&h[(u >> (40 - 12 * level)) & 0xFFF], 1u);
+    // four strided values per thread are loaded before any is counted, so
+    // the loads overlap instead of each waiting for the one before
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t i0 = (int64_t)blockIdx.x * 256 + threadIdx.x; i0 < N; i0 += 4 * stride) {
+        double xs[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) xs[q] = i0 + q * stride < N ? sc[i0 + q * stride] : 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            if (!(xs[q] > 0.0)) continue;
+            const uint64_t u = fx_key(xs[q]);
+            if (level == 1 && ((u >> 40) & 0xFFF) != p0) continue;
+            atomicAdd(&h[(u >> (40 - 12 * level)) & 0xFFF], 1u);
+        }
     }
     __syncthreads();
     uint32_t* hout = a.hist + level * 4096;
