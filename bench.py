@@ -32,9 +32,9 @@ L0_FLOP_PER_SUBSET = 10      # Schur rank-1 extension per 3-subset (see DESIGN.m
 # plain 1 GiB device copy.  Valid only for the kernel source they were taken on.
 SWEEP3_COUNTERS = {
     "source": "paper_2602_06986_amd/csrc/dsc_l0.hip",
-    "sha256": "c1b0a3aad4754614d12925bb6408b336f57f9b63b93acc5910aebaf1201c81ab",
-    "fetch_kib": 250171.5, "fetch_scale": 1.9999,
-    "write_kib": 14776.0, "write_scale": 1.0,
+    "sha256": "b566c12d1f620cbbc85524ffd1aa23f1e1c070de36c41086716e7ab4a9c4ba6c",
+    "fetch_kib": 250155.6, "fetch_scale": 1.9999,
+    "write_kib": 14775.9, "write_scale": 1.0,
 }
 
 
