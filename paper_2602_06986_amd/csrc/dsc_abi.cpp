@@ -25,6 +25,8 @@ extern "C" void discover_destroy(discover_ctx* ctx) {
         if (ctx->side && hipStreamDestroy(ctx->side) != hipSuccess) { /* ignore */ }
         for (auto& kv : ctx->bufs)
             if (kv.second.p && hipFree(kv.second.p) != hipSuccess) { /* ignore */ }
+        for (auto& kv : ctx->pinned)
+            if (kv.second && hipHostFree(kv.second) != hipSuccess) { /* ignore */ }
         for (auto& p : ctx->pending) {
             if (hipEventDestroy(p.a) != hipSuccess || hipEventDestroy(p.b) != hipSuccess) { }
         }

@@ -77,6 +77,19 @@ struct discover_ctx {
         size_t cap = 0;
     };
     std::map<std::string, Buf> bufs;
+    // small pinned host buffers (hipHostMalloc) that kernels write and the
+    // host reads after a synchronisation, kept until the context is destroyed
+    std::map<std::string, void*> pinned;
+    void* pinned_buf(const std::string& name, size_t bytes) {
+        auto it = pinned.find(name);
+        if (it != pinned.end()) return it->second;
+        if (capturing)
+            DSC_FAIL(DISCOVER_E_CAPACITY, "pinned buffer %s would be made during graph capture", name.c_str());
+        void* p = nullptr;
+        DSC_HIP(hipHostMalloc(&p, bytes, hipHostMallocDefault));
+        pinned[name] = p;
+        return p;
+    }
     bool timing = false;
     std::map<std::string, std::pair<int64_t, double>> times;
     struct Pending {
