@@ -1196,12 +1196,25 @@ __global__ __launch_bounds__(256) void k_omp_fit(int n, const double* __restrict
     if (g) {
         double best = -2.0;
         int bi = -1;
-        for (int j = threadIdx.x; j < S; j += 256) {
-            if (!(rownorm[j] > 0.0)) continue;
-            const double v = g[j];
-            if (v > best || (v == best && bi >= 0 && ids[j] < ids[bi])) {
-                best = v;
-                bi = j;
+        // four rows per thread are loaded before any is compared, so the
+        // loads overlap; rows are visited in increasing j as before
+        for (int j0 = threadIdx.x; j0 < S; j0 += 4 * 256) {
+            double nv[4], gv[4];
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const int j = j0 + q * 256;
+                nv[q] = j < S ? rownorm[j] : 0.0;
+                gv[q] = j < S ? g[j] : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const int j = j0 + q * 256;
+                if (!(nv[q] > 0.0)) continue;
+                const double v = gv[q];
+                if (v > best || (v == best && bi >= 0 && ids[j] < ids[bi])) {
+                    best = v;
+                    bi = j;
+                }
             }
         }
         bg[threadIdx.x] = best;
