@@ -32,9 +32,9 @@ L0_FLOP_PER_SUBSET = 10      # Schur rank-1 extension per 3-subset (see DESIGN.m
 # plain 1 GiB device copy.  Valid only for the kernel source they were taken on.
 SWEEP3_COUNTERS = {
     "source": "paper_2602_06986_amd/csrc/dsc_l0.hip",
-    "sha256": "b566c12d1f620cbbc85524ffd1aa23f1e1c070de36c41086716e7ab4a9c4ba6c",
-    "fetch_kib": 250155.6, "fetch_scale": 1.9999,
-    "write_kib": 14775.9, "write_scale": 1.0,
+    "sha256": "1da8f2a03d156bea20ed8157d692064f325934cad07d156c577f2f816e0f6728",
+    "fetch_kib": 250112.5, "fetch_scale": 1.9999,
+    "write_kib": 14776.1, "write_scale": 1.0,
 }
 
 
