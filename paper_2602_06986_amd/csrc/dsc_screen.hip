@@ -1535,10 +1535,10 @@ __device__ __forceinline__ void d_compact(const double* __restrict__ sc, int64_t
                                                  uint32_t* __restrict__ gsel,
                                                  int64_t* __restrict__ gst, double margin,
                                                  int64_t cap, int64_t* __restrict__ pool,
-                                                 unsigned long long* __restrict__ cnt) {
+                                                 unsigned long long* __restrict__ cnt, int64_t K) {
     uint32_t sel[3];
     int64_t st[2];
-    radix_finish(hist, gsel, gst, sel, st);
+    radix_finish1(hist, K, gsel, gst, sel, st);        // one level: a lower bound suffices here
     const double th = select_threshold(sel, st);
     const double lo = st[1] ? 0.0 : th - 2.0 * margin;
     // one atomic per wave: lanes take consecutive slots in lane order; four
@@ -2267,6 +2267,7 @@ struct SelArgs {
     const uint32_t* hist;     // its two level histograms
     double margin;
     int64_t cap, fcap;        // pool and duplicate-pair capacities
+    int64_t K;                // rank the radix selection bounds
     int64_t* pool;
     unsigned long long* cnt;  // pool entries found (may exceed cap)
     EvalCtx ev;
@@ -2297,7 +2298,7 @@ struct SelArgs {
 __global__ __launch_bounds__(256) void k_compact(ctab<SelArgs> A) {
     const SelArgs& a = tab(A, blockIdx.y);
     DSC_GLOBAL(a.sc); DSC_GLOBAL(a.sel); DSC_GLOBAL(a.st); DSC_GLOBAL(a.pool); DSC_GLOBAL(a.cnt); DSC_GLOBAL(a.ev.raw2c); DSC_GLOBAL(a.ev.valid); DSC_GLOBAL(a.o.Vf); DSC_GLOBAL(a.o.Rf); DSC_GLOBAL(a.Yc); DSC_GLOBAL(a.syy); DSC_GLOBAL(a.ps); DSC_GLOBAL(a.pex); DSC_GLOBAL(a.maxerr); DSC_GLOBAL(a.order); DSC_GLOBAL(a.lo); DSC_GLOBAL(a.wc); DSC_GLOBAL(a.off); DSC_GLOBAL(a.flag); DSC_GLOBAL(a.parent); DSC_GLOBAL(a.blk); DSC_GLOBAL(a.repid); DSC_GLOBAL(a.reppos); DSC_GLOBAL(a.headpos); DSC_GLOBAL(a.out_ids); DSC_GLOBAL(a.out_sc); DSC_GLOBAL(a.res);
-    d_compact(a.sc, a.N, a.hist, a.sel, a.st, a.margin, a.cap, a.pool, a.cnt);
+    d_compact(a.sc, a.N, a.hist, a.sel, a.st, a.margin, a.cap, a.pool, a.cnt, a.K);
 }
 
 __global__ __launch_bounds__(256) void k_rescore(ctab<SelArgs> A) {
@@ -3149,7 +3150,7 @@ static void select_round(discover_ctx* ctx, const discover_problem* probs,
         uint32_t* sel = (uint32_t*)(misc + 32);
         a.sel = sel; a.st = stv; a.hist = hist;
         a.sc = P.scores + (int64_t)L.t * P.N; a.N = P.N;
-        a.margin = margin[L.b]; a.cap = L.cap; a.fcap = L.fcap;
+        a.margin = margin[L.b]; a.cap = L.cap; a.fcap = L.fcap; a.K = L.K;
         a.ev = P.ev(); a.o = P.ops(); a.n = P.n; a.T = P.T; a.mode = prm.score_mode; a.t = L.t;
         a.k = k; a.dedup = prm.dedup;
         a.Yc = P.Yc; a.syy = P.syy;
@@ -3168,7 +3169,7 @@ static void select_round(discover_ctx* ctx, const discover_problem* probs,
     const RadixArgs* dra = ctx->upload("sel_radix", ra, st);
     {
         KTimer kt(ctx, st, "select");
-        radix_select(dra, nl, Nmax, st);
+        radix_select(dra, nl, Nmax, st, 1);
     }
     const unsigned hb = (unsigned)std::min<int64_t>(1024, std::max<int64_t>(1, cdiv(Nmax, 256 * 8)));
     k_compact<<<dim3(hb, nl), 256, 0, st>>>(dsa);

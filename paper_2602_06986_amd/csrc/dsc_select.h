@@ -1,8 +1,8 @@
-// Radix selection of a lower bound of the K-th largest positive value: two
-// 12-bit levels of a fixed-point key.  Its users need only a bound at most
-// the K-th value (the screening pool and the L0 band reach below it by
-// their own margins), and two levels bound it within 2^-24.  Shared by the
-// screening pool and the L0 band.
+// Radix selection of a lower bound of the K-th largest positive value: one
+// or two 12-bit levels of a fixed-point key.  Its users need only a bound
+// at most the K-th value (the screening pool and the L0 band reach below it
+// by their own margins); one level bounds it within 2^-12 (the screening
+// pool), two within 2^-24 (the L0 band, whose refits grow with the band).
 #pragma once
 
 #include <algorithm>
@@ -135,6 +135,24 @@ static __global__ __launch_bounds__(256) void k_hist(ctab<RadixArgs> A, int leve
         if (h[b]) atomicAdd(&hout[b], h[b]);
 }
 
+// One level only: the consumer reads the level-0 digit for rank K (a lower
+// bound within 2^-12 of the K-th value); sel[1] stays 0.
+static __device__ __forceinline__ void radix_finish1(const uint32_t* __restrict__ hist, int64_t K,
+                                                     uint32_t* __restrict__ gsel, int64_t* __restrict__ gst,
+                                                     uint32_t (&sel)[3], int64_t (&st)[2]) {
+    const RadixDigit d0 = radix_digit(hist, K, false);
+    sel[0] = d0.all ? 0u : d0.digit;
+    sel[1] = 0u;
+    sel[2] = 0u;
+    st[0] = d0.rank;
+    st[1] = d0.all ? 1 : 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        gsel[0] = sel[0];
+        gst[0] = st[0];
+        gst[1] = st[1];
+    }
+}
+
 // The selection's consumer: every block reads the level-1 digit into sel
 // and st (its own copies); block 0 publishes them for later kernels.
 static __device__ __forceinline__ void radix_finish(const uint32_t* __restrict__ hist,
@@ -163,11 +181,12 @@ static __device__ __forceinline__ double select_threshold(const uint32_t* sel, c
 // Launch the histograms of the selections of nl lists (device table A;
 // each list's hist, st and sel zero); the consumer's radix_finish then
 // gives the K-th largest positive entry of each list.
-static inline void radix_select(const RadixArgs* Ad, int nl, int64_t Nmax, hipStream_t s) {
+static inline void radix_select(const RadixArgs* Ad, int nl, int64_t Nmax, hipStream_t s,
+                                int levels = RADIX_LEVELS) {
     if (nl <= 0) return;
     const ctab<RadixArgs> A = ct(Ad);
     const unsigned hb = (unsigned)std::min<int64_t>(1024, std::max<int64_t>(1, cdiv(Nmax, 256 * 8)));
-    for (int level = 0; level < RADIX_LEVELS; level++) k_hist<<<dim3(hb, nl), 256, 0, s>>>(A, level);
+    for (int level = 0; level < levels; level++) k_hist<<<dim3(hb, nl), 256, 0, s>>>(A, level);
     check_launch("radix_select");
 }
 
