@@ -265,8 +265,6 @@ constexpr int SW3_A = 4;              // values of a per wave
 constexpr int SW3_MMAX = 16;          // bounded sweep for m up to this
 // (2^-24: the radix selection's threshold may lie that far below the m-th lane value)
 constexpr double SW3_TH_SLACK = GRAM_DELTA + 4.0 * SW3_RCP_DELTA + 5.9604644775390625e-8 + 1e-8;
-// high word of PIV_TOL: den > PIV_TOL implies hi(den) >= SW3_HI_PIV
-constexpr int SW3_HI_PIV = (int)(__builtin_bit_cast(unsigned long long, PIV_TOL) >> 32);
 
 struct Sw3Lane {
     double upc, dc, zc;
