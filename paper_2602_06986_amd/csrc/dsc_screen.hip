@@ -19,6 +19,7 @@
 //
 // The streamed rung is never materialised: each wave evaluates
 // op(f_i, f_j) for its tile on the fly and keeps only moments in registers.
+#include <functional>
 #include "dsc_internal.h"
 #include "dsc_select.h"
 #include "dsc_space.h"
@@ -2826,7 +2827,8 @@ static int tune_dense(discover_ctx* ctx, const std::string& key, int cls, int TP
 // Materialise the operand features of every problem and screen every
 // candidate into its score slots (no host synchronisation).
 static void screen_all(discover_ctx* ctx, const discover_problem* probs, int nb,
-                       const discover_screen_params& prm, std::vector<Problem>& PS, hipStream_t st) {
+                       const discover_screen_params& prm, std::vector<Problem>& PS, hipStream_t st,
+                       const std::function<void(std::vector<FillSeg>&)>& more_fills = nullptr) {
     layout_problems(ctx, probs, nb, prm, PS);
     // 1. fills: counters, padded target rows, score slots (NaN pattern), rung-2 flags
     std::vector<FillSeg> fills;
@@ -2837,6 +2839,7 @@ static void screen_all(discover_ctx* ctx, const discover_problem* probs, int nb,
         fills.push_back(fill_seg(P.scores, (size_t)P.Tl * P.N * 8, 0xFFFFFFFFu));
         if (P.r2v) fills.push_back(fill_seg(P.r2v, ((size_t)P.plan->sp.d.L[2] + 3) & ~size_t(3), 0u));
     }
+    if (more_fills) more_fills(fills);                  // e.g. the first selection round's counters
     fill_all(ctx, "scr_fills", fills, st);
     // 2. targets
     std::vector<TgtArgs> ta(nb);
@@ -3084,15 +3087,16 @@ static void screen_all(discover_ctx* ctx, const discover_problem* probs, int nb,
 // holds every candidate whose score can reach its K-th largest approximate
 // score minus the error margin; it is rescored exactly and grouped in
 // (-score, ID) order.
-static void select_round(discover_ctx* ctx, const discover_problem* probs,
-                         const discover_screen_params& prm, std::vector<Problem>& PS,
-                         const std::vector<ListState>& LS, const std::vector<int>& act,
-                         const std::vector<double>& margin, const std::vector<ScreenOut>& outs,
-                         hipStream_t st, std::vector<SelArgs>& sa) {
+// Layout of one selection round's arena: per active list, the offsets of
+// its arrays (pool, scores, ..., counters at SEL_MISC, histograms at
+// SEL_HIST, stored pool values).
+constexpr int SEL_MISC = 17, SEL_HIST = 18;
+
+static char* sel_layout(discover_ctx* ctx, int k, const std::vector<ListState>& LS,
+                        const std::vector<int>& act, std::vector<std::vector<size_t>>& o) {
     const int nl = (int)act.size();
-    const int k = prm.k;
     Arena ar;
-    std::vector<std::vector<size_t>> o(nl);
+    o.assign(nl, {});
     for (int q = 0; q < nl; q++) {
         const ListState& L = LS[act[q]];
         const size_t cap = (size_t)L.cap, fcap = (size_t)L.fcap;
@@ -3121,7 +3125,18 @@ static void select_round(discover_ctx* ctx, const discover_problem* probs,
         v.push_back(ar.add(pvc * 8));              // their means
         v.push_back(ar.add(pvc * 8));              // their centred sums of squares
     }
-    char* base = (char*)ctx->raw("sel_arena" + ctx->tag, ar.total);
+    return (char*)ctx->raw("sel_arena" + ctx->tag, ar.total);
+}
+
+static void select_round(discover_ctx* ctx, const discover_problem* probs,
+                         const discover_screen_params& prm, std::vector<Problem>& PS,
+                         const std::vector<ListState>& LS, const std::vector<int>& act,
+                         const std::vector<double>& margin, const std::vector<ScreenOut>& outs,
+                         hipStream_t st, std::vector<SelArgs>& sa, bool prefilled = false) {
+    const int nl = (int)act.size();
+    const int k = prm.k;
+    std::vector<std::vector<size_t>> o;
+    char* base = sel_layout(ctx, k, LS, act, o);
     sa.assign(nl, SelArgs{});
     std::vector<RadixArgs> ra(nl);
     std::vector<FillSeg> fills;
@@ -3164,7 +3179,7 @@ static void select_round(discover_ctx* ctx, const discover_problem* probs,
         capmax = std::max(capmax, L.cap);
         Kmax = std::max(Kmax, L.K);
     }
-    fill_all(ctx, "sel_fills", fills, st);
+    if (!prefilled) fill_all(ctx, "sel_fills", fills, st);     // else cleared with the screen's fills
     const ctab<SelArgs> dsa = ct(ctx->upload("sel_args", sa, st));
     const RadixArgs* dra = ctx->upload("sel_radix", ra, st);
     {
@@ -3280,10 +3295,42 @@ void generate_screen(discover_ctx* ctx, const discover_problem* probs, int nb,
                      const discover_screen_params& prm, const std::vector<ScreenOut>& outs,
                      discover_screen_stats* out_stats, hipStream_t st, std::vector<ListCheck>* checks) {
     std::vector<Problem> PS;
-    screen_all(ctx, probs, nb, prm, PS, st);
+    std::vector<ListState> LS;
+    std::vector<int> act;
+    const std::string ck = call_key(probs, nb, prm);
+    // the lists and the first selection round's arena are laid out before
+    // the screen, so that round's counters and histograms are cleared by the
+    // screen's own fill launch
+    auto first_round = [&](std::vector<FillSeg>& fills) {
+        for (int b = 0; b < nb; b++) {
+            const Problem& P = PS[b];
+            for (int t = 0; t < P.Tl; t++) {
+                ListState L;
+                L.b = b; L.t = t; L.n = P.n;
+                L.K = 2 * (int64_t)prm.k + probs[b].n_exclude + 64;
+                L.cap = 4 * L.K + 4096;
+                L.fcap = 64 * L.cap;
+                LS.push_back(L);
+            }
+        }
+        auto mit = ctx->batches.find("sel" + ck);
+        if (mit != ctx->batches.end()) {        // start from the sizes a previous call settled on
+            const SelMemo& m = *std::static_pointer_cast<SelMemo>(mit->second);
+            if (m.K.size() == LS.size())
+                for (size_t l = 0; l < LS.size(); l++) { LS[l].K = m.K[l]; LS[l].cap = m.cap[l]; LS[l].fcap = m.fcap[l]; }
+        }
+        act.resize(LS.size());
+        for (size_t l = 0; l < LS.size(); l++) act[l] = (int)l;
+        std::vector<std::vector<size_t>> o;
+        char* base = sel_layout(ctx, prm.k, LS, act, o);
+        for (size_t q = 0; q < act.size(); q++) {
+            fills.push_back(fill_seg(base + o[q][SEL_MISC], 48, 0u));   // pool count, maximum error, st, sel
+            fills.push_back(fill_seg(base + o[q][SEL_HIST], 8192 * 4, 0u));
+        }
+    };
+    screen_all(ctx, probs, nb, prm, PS, st, first_round);
     std::vector<discover_screen_stats> stats(nb);
     std::vector<double> margin(nb);
-    std::vector<ListState> LS;
     for (int b = 0; b < nb; b++) {
         const Problem& P = PS[b];
         discover_screen_stats& s = stats[b];
@@ -3296,28 +3343,13 @@ void generate_screen(discover_ctx* ctx, const discover_problem* probs, int nb,
             s.guard_band = lowprec_margin(prm.precision, P.n);
             margin[b] = std::max(margin[b], s.guard_band);
         }
-        for (int t = 0; t < P.Tl; t++) {
-            ListState L;
-            L.b = b; L.t = t; L.n = P.n;
-            L.K = 2 * (int64_t)prm.k + probs[b].n_exclude + 64;
-            L.cap = 4 * L.K + 4096;
-            L.fcap = 64 * L.cap;
-            LS.push_back(L);
-        }
     }
-    const std::string ck = call_key(probs, nb, prm);
-    auto mit = ctx->batches.find("sel" + ck);
-    if (mit != ctx->batches.end()) {            // start from the sizes a previous call settled on
-        const SelMemo& m = *std::static_pointer_cast<SelMemo>(mit->second);
-        if (m.K.size() == LS.size())
-            for (size_t l = 0; l < LS.size(); l++) { LS[l].K = m.K[l]; LS[l].cap = m.cap[l]; LS[l].fcap = m.fcap[l]; }
-    }
-    std::vector<int> act(LS.size());
-    for (size_t l = 0; l < LS.size(); l++) act[l] = (int)l;
     std::vector<SelArgs> sa;
     bool checked_bad = false;
+    bool prefilled = true;
     while (!act.empty()) {
-        select_round(ctx, probs, prm, PS, LS, act, margin, outs, st, sa);
+        select_round(ctx, probs, prm, PS, LS, act, margin, outs, st, sa, prefilled);
+        prefilled = false;
         if (ctx->capturing) {                   // results are checked after the replay
             if (checks)
                 for (size_t q = 0; q < act.size(); q++) {
