@@ -84,7 +84,7 @@ static void sisso_sequence(discover_ctx* ctx, const SissoCall& c, const std::str
     fills.push_back(fill_seg(verdict, 4, 0u));
     fills.push_back(fill_seg(c.sub, (size_t)nb * D * m * 3 * 4, 0xFFFFFFFFu));
     fills.push_back(fill_seg(c.coef, (size_t)nb * D * m * 4 * 8, 0xFFFFFFFFu));   // NaN
-    fill_all(ctx, "sis_fills", fills, st);
+    // (cleared by dimension 1's screen fill launch, which precedes every use)
     std::vector<ListCheck> lc;
     std::vector<BandCheck> bc;
     std::vector<discover_l0_stats> l0st(nb);
@@ -112,7 +112,8 @@ static void sisso_sequence(discover_ctx* ctx, const SissoCall& c, const std::str
         }
         discover_screen_params q = c.prm;
         if (d > 1 && m > 1) q.score_mode = DISCOVER_SCORE_MAX;
-        generate_screen(ctx, sp.data(), nb, q, so, nullptr, st, ctx->capturing ? &lc : nullptr);
+        generate_screen(ctx, sp.data(), nb, q, so, nullptr, st, ctx->capturing ? &lc : nullptr,
+                        d == 1 ? &fills : nullptr);
         std::vector<discover_l0_problem> lp(nb);
         std::vector<L0Out> lo(nb);
         for (int b = 0; b < nb; b++) {

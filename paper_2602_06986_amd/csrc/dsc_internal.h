@@ -48,10 +48,12 @@ struct BandCheck {
 // Screening of every problem of a call (validated arguments).  Outside
 // capture the call synchronises and fills out_stats; while capturing it
 // records the checks instead.
+// extra_fills: more buffers to clear with the screen's own fill launch.
 void generate_screen(discover_ctx* ctx, const discover_problem* probs, int nb,
                      const discover_screen_params& prm, const std::vector<ScreenOut>& outs,
                      discover_screen_stats* out_stats, hipStream_t st,
-                     std::vector<ListCheck>* checks = nullptr);
+                     std::vector<ListCheck>* checks = nullptr,
+                     const std::vector<FillSeg>* extra_fills = nullptr);
 
 // Exhaustive L0 of every problem of a call (validated arguments).
 void l0_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D, int m,

@@ -3293,7 +3293,8 @@ static std::string call_key(const discover_problem* probs, int nb, const discove
 
 void generate_screen(discover_ctx* ctx, const discover_problem* probs, int nb,
                      const discover_screen_params& prm, const std::vector<ScreenOut>& outs,
-                     discover_screen_stats* out_stats, hipStream_t st, std::vector<ListCheck>* checks) {
+                     discover_screen_stats* out_stats, hipStream_t st, std::vector<ListCheck>* checks,
+                     const std::vector<FillSeg>* extra_fills) {
     std::vector<Problem> PS;
     std::vector<ListState> LS;
     std::vector<int> act;
@@ -3302,6 +3303,7 @@ void generate_screen(discover_ctx* ctx, const discover_problem* probs, int nb,
     // the screen, so that round's counters and histograms are cleared by the
     // screen's own fill launch
     auto first_round = [&](std::vector<FillSeg>& fills) {
+        if (extra_fills) fills.insert(fills.end(), extra_fills->begin(), extra_fills->end());
         for (int b = 0; b < nb; b++) {
             const Problem& P = PS[b];
             for (int t = 0; t < P.Tl; t++) {
