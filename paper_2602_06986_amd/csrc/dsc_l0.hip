@@ -955,6 +955,8 @@ struct PrepArgs {
     const double* y;
     double *Z, *G, *yy;
     double* dg;               // G's diagonal, contiguous (written by the Gram kernel)
+    uint32_t* clr;            // words the standardising kernel clears (the band's first-round counters)
+    int64_t clr_n32;
     double4* E;               // D = 3 factor table
     int lde;
     const double* theta;      // D = 3: shift th of the table's Q_ab
@@ -964,6 +966,8 @@ struct PrepArgs {
 __global__ __launch_bounds__(256) void k_l0_prep(ctab<PrepArgs> A) {
     const PrepArgs& a = tab(A, blockIdx.y);
     DSC_GLOBAL(a.F); DSC_GLOBAL(a.y); DSC_GLOBAL(a.Z); DSC_GLOBAL(a.yy);
+    for (int64_t w = (int64_t)blockIdx.x * 256 + threadIdx.x; w < a.clr_n32; w += (int64_t)gridDim.x * 256)
+        a.clr[w] = 0u;
     if ((int)blockIdx.x * 4 > a.S) return;
     d_l0_prep(a.n, a.S, a.F, a.ldf, a.y, a.ldz, a.Z, a.yy);
 }
@@ -1398,6 +1402,31 @@ void l0_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D
         pa[b].theta = (const double*)(base + o[b][4]);
         pa[b].dg = (double*)(base + o[b][7]);
     }
+    // the band's first-round arena is laid out now, so that its counters and
+    // radix histograms are cleared by the standardising kernel
+    std::vector<int64_t> cap(nb, std::max<int64_t>(1 << 16, 256 * (int64_t)m));
+    std::string ck((const char*)&D, sizeof D);
+    ck.append((const char*)&m, sizeof m);
+    for (int b = 0; b < nb; b++) {
+        const int64_t f[5] = {probs[b].n, probs[b].S, (int64_t)(intptr_t)probs[b].F,
+                              (int64_t)(intptr_t)probs[b].y, (int64_t)(intptr_t)probs[b].ids};
+        ck.append((const char*)f, sizeof f);
+    }
+    auto mit = ctx->batches.find("band" + ck);
+    if (mit != ctx->batches.end()) {
+        const BandMemo& bm = *std::static_pointer_cast<BandMemo>(mit->second);
+        if ((int)bm.cap.size() == nb) cap = bm.cap;
+    }
+    std::vector<int> act(nb);
+    for (int b = 0; b < nb; b++) act[b] = b;
+    {
+        std::vector<std::vector<size_t>> bo0;
+        char* bb0 = (char*)ctx->raw("l0_band_arena" + ctx->tag, band_arena_bytes(act, cap, D, m, &bo0));
+        for (int b = 0; b < nb; b++) {                  // counters and histograms are adjacent
+            pa[b].clr = (uint32_t*)(bb0 + bo0[b][6]);
+            pa[b].clr_n32 = (int64_t)(bo0[b][7] + 8192 * 4 - bo0[b][6]) / 4;
+        }
+    }
     const ctab<PrepArgs> dpa = ct(ctx->upload("l0_prep", pa, st));
     const bool bound = D == 3 && m <= SW3_MMAX;
     // 2. Gram matrices (and the D = 3 factor tables)
@@ -1472,27 +1501,13 @@ void l0_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D
         check_launch("k_sweep");
     }
     // 4. band: radix selection of the m-th best lane, expansion, QR refit, ranking
-    std::vector<int64_t> cap(nb, std::max<int64_t>(1 << 16, 256 * (int64_t)m));
-    std::string ck((const char*)&D, sizeof D);
-    ck.append((const char*)&m, sizeof m);
-    for (int b = 0; b < nb; b++) {
-        const int64_t f[5] = {probs[b].n, probs[b].S, (int64_t)(intptr_t)probs[b].F,
-                              (int64_t)(intptr_t)probs[b].y, (int64_t)(intptr_t)probs[b].ids};
-        ck.append((const char*)f, sizeof f);
-    }
-    auto mit = ctx->batches.find("band" + ck);
-    if (mit != ctx->batches.end()) {
-        const BandMemo& bm = *std::static_pointer_cast<BandMemo>(mit->second);
-        if ((int)bm.cap.size() == nb) cap = bm.cap;
-    }
-    std::vector<int> act(nb);
-    for (int b = 0; b < nb; b++) act[b] = b;
     constexpr int NREFIT = 2048;                // persistent refit workgroups (all problems)
     int nmax = 0;
     for (int b = 0; b < nb; b++) nmax = std::max(nmax, probs[b].n);
     const int64_t sld = (int64_t)(D + 2) * nmax;
     double* rscratch = ctx->buf<double>("l0_refit_scratch", (size_t)NREFIT * sld);
     int64_t* boff = ctx->buf<int64_t>("l0_boff" + ctx->tag, (size_t)nb + 1);
+    bool prefilled = true;                      // the first round's counters: cleared by k_l0_prep
     while (!act.empty()) {
         const int na = (int)act.size();
         std::vector<std::vector<size_t>> bo;
@@ -1534,7 +1549,8 @@ void l0_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D
             f.out_resid = outs[b].resid;
             f.ldr = outs[b].ldr;
         }
-        fill_all(ctx, "l0_fills", fills, st);
+        if (!prefilled) fill_all(ctx, "l0_fills", fills, st);
+        prefilled = false;
         const ctab<BandArgs> dba = ct(ctx->upload("l0_band", ba, st));
         const RadixArgs* dra = ctx->upload("l0_radix", ra, st);
         const ctab<RefitArgs> dfa = ct(ctx->upload("l0_refit", fa, st));
