@@ -32,9 +32,9 @@ L0_FLOP_PER_SUBSET = 10      # Schur rank-1 extension per 3-subset (see DESIGN.m
 # plain 1 GiB device copy.  Valid only for the kernel source they were taken on.
 SWEEP3_COUNTERS = {
     "source": "paper_2602_06986_amd/csrc/dsc_l0.hip",
-    "sha256": "53a6bbf532c472148f3fcaf361a21872ecbf4ff6e3442153b93324d1de73f110",
-    "fetch_kib": 250111.7, "fetch_scale": 1.9999,
-    "write_kib": 14776.1, "write_scale": 1.0,
+    "sha256": "6b85913564e48d84f4882dbd5d1d44e1d100106d54afdb5f8467d37225652fa4",
+    "fetch_kib": 250071.4, "fetch_scale": 1.9999,
+    "write_kib": 14776.0, "write_scale": 1.0,
 }
 
 
