@@ -2061,7 +2061,7 @@ __device__ __forceinline__ void d_groups_lds(
     const uint8_t* __restrict__ flag, int64_t P, int64_t flag_cap, int k, int dedup,
     const uint32_t* __restrict__ sel, const int64_t* __restrict__ st, double margin,
     int32_t* __restrict__ headpos, int64_t* __restrict__ out_ids, double* __restrict__ out_sc,
-    int64_t* __restrict__ res, int64_t total_flags) {
+    int64_t* __restrict__ res, int64_t total_flags, const PoolVals pvs, int64_t* __restrict__ vrow) {
     __shared__ int64_t part[GRP_THREADS];
     __shared__ __align__(16) int32_t par[GRP_LDS];
     __shared__ __align__(16) unsigned long long rkey[GRP_LDS];   // also the sort array of phase 5
@@ -2147,10 +2147,12 @@ __device__ __forceinline__ void d_groups_lds(
     if (ns <= GRP_THREADS) {
         int N2 = 1;
         while (N2 < ns) N2 <<= 1;
+        // the key keeps its sorted-position bits below the ID: distinct IDs
+        // order the keys as they order the IDs
         SK e{-INFINITY, INT64_MAX};                               // padding sorts last
         if (t < ns) {
             const unsigned long long kk = rkey[headpos[t]];
-            e = SK{ps[order[(int)(kk & 4095ull)]], (long long)(kk >> 12)};
+            e = SK{ps[order[(int)(kk & 4095ull)]], (long long)kk};
         }
         SK* srt = (SK*)rkey;                                      // 1024 entries = 16 KB
         for (int kb = 2; kb <= N2; kb <<= 1)
@@ -2172,8 +2174,10 @@ __device__ __forceinline__ void d_groups_lds(
                 if (o_first == keep_first) e = o;
             }
         if (t < ns) {
-            out_ids[t] = e.id;
+            const int32_t slot = order[(int)((unsigned long long)e.id & 4095ull)];
+            out_ids[t] = e.id >> 12;
             out_sc[t] = e.s;
+            vrow[t] = slot < pvs.cap ? (int64_t)(uintptr_t)(pvs.v + (int64_t)slot * pvs.ld) : 0;
         }
     } else {
     SK* tile = (SK*)par;                                          // 1024 entries = 16 KB
@@ -2200,9 +2204,12 @@ __device__ __forceinline__ void d_groups_lds(
         if (i < ns) {
             out_ids[rank] = ii;
             out_sc[rank] = si;
+            const int32_t slot = order[(int)(rkey[headpos[i]] & 4095ull)];
+            vrow[rank] = slot < pvs.cap ? (int64_t)(uintptr_t)(pvs.v + (int64_t)slot * pvs.ld) : 0;
         }
     }
     }
+    for (int64_t i = ns + t; i < k; i += GRP_THREADS) vrow[i] = 0;
     for (int64_t i = ns + t; i < k; i += GRP_THREADS) {
         out_ids[i] = -1;
         out_sc[i] = __longlong_as_double(0x7FF8000000000000LL);
@@ -2220,14 +2227,22 @@ __device__ __forceinline__ void d_groups_lds(
     }
 }
 
-// Values of the selected candidates: one wave per output row.
+// Values of the selected candidates: one wave per output row; a row whose
+// values the exact rescoring kept (the same numbers) is copied.
 __device__ __forceinline__ void d_values(const int64_t* __restrict__ ids, int64_t m,
                                                 const EvalCtx& ev, Ops o, int n,
-                                                double* __restrict__ out, int64_t ldv) {
+                                                double* __restrict__ out, int64_t ldv,
+                                                const int64_t* __restrict__ vrow) {
     const int64_t w = (int64_t)blockIdx.x * 4 + wave_id();
     if (w >= m) return;
     const int lane = threadIdx.x & 63;
     const int64_t id = ids[w];
+    const int64_t src = vrow && id >= 0 ? vrow[w] : 0;
+    if (src) {                                          // (wave-uniform)
+        const double* v = (const double*)(uintptr_t)src;
+        for (int i = lane; i < n; i += 64) out[w * ldv + i] = v[i];
+        return;
+    }
     Cand c;
     const bool ok = id >= 0 && cand_of_id(ev, id, c);
     for (int i = lane; i < n; i += 64)
@@ -2293,6 +2308,7 @@ struct SelArgs {
     double* out_sc;
     int64_t* res;
     PoolVals pvs;             // stored values of the first pvs.cap pool entries
+    int64_t* vrow;            // per selected rank: address of its stored value row, 0 for none
 };
 
 // grid (blocks, lists) for the streaming kernels, (lists) for the one-block ones
@@ -2361,10 +2377,12 @@ __global__ __launch_bounds__(GRP_THREADS) void k_groups(ctab<SelArgs> A) {
     }
     if (P <= GRP_LDS) {
         d_groups_lds(a.pool, a.ps, a.pex, a.order, a.lo, a.off, a.flag, P, a.fcap, a.k, a.dedup, a.sel,
-                     a.st, a.margin, a.headpos, a.out_ids, a.out_sc, a.res, P > 0 ? a.off[P] : 0);
+                     a.st, a.margin, a.headpos, a.out_ids, a.out_sc, a.res, P > 0 ? a.off[P] : 0, a.pvs,
+                     a.vrow);
         if (threadIdx.x == 0) a.res[4] = (int64_t)*a.cnt;     // pool size (capacity check)
         return;
     }
+    for (int64_t i = threadIdx.x; i < a.k; i += GRP_THREADS) a.vrow[i] = 0;   // rows are evaluated
     d_groups(a.pool, a.ps, a.pex, a.order, a.lo, a.off, a.flag, a.cnt, a.cap, a.fcap, a.k, a.dedup,
              a.sel, a.st, a.margin, a.parent, a.blk, a.repid, a.reppos, a.headpos, a.out_ids,
              a.out_sc, a.res);
@@ -2379,6 +2397,7 @@ struct ValArgs {
     int n;
     double* out;
     int64_t ldv;
+    const int64_t* vrow;      // or NULL: per row, the address of its stored values (0: evaluate)
 };
 
 // grid (row blocks of 4, lists)
@@ -2386,7 +2405,7 @@ __global__ __launch_bounds__(256) void k_values(ctab<ValArgs> A) {
     const ValArgs& a = tab(A, blockIdx.y);
     DSC_GLOBAL(a.ids); DSC_GLOBAL(a.ev.raw2c); DSC_GLOBAL(a.ev.valid); DSC_GLOBAL(a.o.Vf); DSC_GLOBAL(a.o.Rf); DSC_GLOBAL(a.out);
     if ((int64_t)blockIdx.x * 4 >= a.m) return;
-    d_values(a.ids, a.m, a.ev, a.o, a.n, a.out, a.ldv);
+    d_values(a.ids, a.m, a.ev, a.o, a.n, a.out, a.ldv, a.vrow);
 }
 
 }  // namespace dsc
@@ -3141,6 +3160,9 @@ static void select_round(discover_ctx* ctx, const discover_problem* probs,
     std::vector<RadixArgs> ra(nl);
     std::vector<FillSeg> fills;
     int64_t Nmax = 1, capmax = 1, Kmax = 1;
+    std::vector<int64_t> vbase(PS.size() + 1, 0);              // value-row addresses, laid out as the IDs
+    for (size_t b = 0; b < PS.size(); b++) vbase[b + 1] = vbase[b] + (int64_t)PS[b].Tl * k;
+    int64_t* vrow = ctx->buf<int64_t>("scr_vrow" + ctx->tag, (size_t)vbase.back());
     for (int q = 0; q < nl; q++) {
         const ListState& L = LS[act[q]];
         const Problem& P = PS[L.b];
@@ -3172,6 +3194,7 @@ static void select_round(discover_ctx* ctx, const discover_problem* probs,
         a.excl = pb.exclude; a.n_excl = pb.exclude ? pb.n_exclude : 0;
         a.out_ids = outs[L.b].ids + (int64_t)L.t * k;
         a.out_sc = outs[L.b].sc + (int64_t)L.t * k;
+        a.vrow = vrow + vbase[L.b] + (int64_t)L.t * k;
         ra[q] = RadixArgs{a.sc, P.N, L.K, hist, sel, stv, nullptr};
         fills.push_back(fill_seg(misc, 48, 0u));            // pool count, maximum error, st, sel
         fills.push_back(fill_seg(hist, 8192 * 4, 0u));
@@ -3349,9 +3372,11 @@ void generate_screen(discover_ctx* ctx, const discover_problem* probs, int nb,
     std::vector<SelArgs> sa;
     bool checked_bad = false;
     bool prefilled = true;
+    int rounds = 0;
     while (!act.empty()) {
         select_round(ctx, probs, prm, PS, LS, act, margin, outs, st, sa, prefilled);
         prefilled = false;
+        rounds++;
         if (ctx->capturing) {                   // results are checked after the replay
             if (checks)
                 for (size_t q = 0; q < act.size(); q++) {
@@ -3419,6 +3444,7 @@ void generate_screen(discover_ctx* ctx, const discover_problem* probs, int nb,
         }
         act.swap(next);
     }
+    const auto gen0 = ctx->generation;
     if (!ctx->capturing) {
         // size the result arena for a one-round run of every list at the final
         // capacities, as a captured run does
@@ -3431,11 +3457,18 @@ void generate_screen(discover_ctx* ctx, const discover_problem* probs, int nb,
     if (outs[0].vals) {
         std::vector<ValArgs> va;
         int64_t mmax = 0;
+        // after one selection round every list's stored pool values are still
+        // in place (a later round lays the arena out anew, a regrown arena
+        // is a new allocation)
+        const int64_t* vrow = rounds == 1 && ctx->generation == gen0 ? ctx->buf<int64_t>("scr_vrow" + ctx->tag, 0) : nullptr;
+        int64_t voff = 0;
         for (int b = 0; b < nb; b++) {
             const Problem& P = PS[b];
             ValArgs a{};
             a.ids = outs[b].ids; a.m = (int64_t)P.Tl * prm.k; a.ev = P.ev(); a.o = P.ops();
             a.n = P.n; a.out = outs[b].vals; a.ldv = outs[b].ldv;
+            a.vrow = vrow ? vrow + voff : nullptr;
+            voff += a.m;
             va.push_back(a);
             mmax = std::max(mmax, a.m);
         }
