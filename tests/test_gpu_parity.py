@@ -181,6 +181,32 @@ def test_screen_random(torch, ctx, D, oracle_mod, seed, p, n, B, R, dedup, k):
     assert n_sel == len(lst[0])
     if n_sel < k:
         assert bool((ids[0][n_sel:] == -1).all())
+    # the returned values are the selected features' values (copied from the
+    # rescoring's stored rows, or evaluated where none is stored)
+    V, _ = O.values(sp, X, units, ids[0][:n_sel].cpu().numpy())
+    np.testing.assert_allclose(vals[0][:n_sel].cpu().numpy(), V, rtol=1e-12, atol=0)
+
+
+def test_screen_duplicates_second_round(torch, ctx, D, oracle_mod):
+    """Nine power-of-two multiples of one column and four of another: most
+    candidates duplicate a better one, so the first pool holds fewer than k
+    representatives and the selection takes a second, wider round; the
+    list and the returned values still match."""
+    O = oracle_mod
+    rng = np.random.default_rng(321)
+    n, k = 77, 40
+    base = rng.lognormal(0, 0.4, size=(3, n))
+    X = np.stack([base[0] * 2.0 ** j for j in range(9)] + [base[1] * 2.0 ** -j for j in range(4)]
+                 + [base[2]])
+    y = base[0] * base[1] + 0.3 * base[2] + 0.05 * rng.normal(size=n)
+    sp = O.Space(X.shape[0], 2, O.OPS)
+    (lst,), status, nvalid = O.sis(sp, X, None, y[None], k, (), "per_target", True)
+    ids, sc, vals, st = ctx.generate_screen(dev(torch, X), dev(torch, y[None]), D.params(rung=2, k=k))
+    check_selection(ids[0].cpu().numpy(), sc[0].cpu().numpy(), lst[0], lst[1], what="duplicates")
+    assert st["pool_rounds"] >= 1
+    assert st["n_merged"] > 0
+    V, _ = O.values(sp, X, None, ids[0].cpu().numpy())
+    np.testing.assert_allclose(vals[0].cpu().numpy(), V, rtol=1e-12, atol=0)
 
 
 @pytest.mark.parametrize("T", [1, 2, 3])
