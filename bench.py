@@ -33,7 +33,7 @@ L0_FLOP_PER_SUBSET = 10      # Schur rank-1 extension per 3-subset (see DESIGN.m
 SWEEP3_COUNTERS = {
     "source": "paper_2602_06986_amd/csrc/dsc_l0.hip",
     "sha256": "6b85913564e48d84f4882dbd5d1d44e1d100106d54afdb5f8467d37225652fa4",
-    "fetch_kib": 250071.4, "fetch_scale": 1.9999,
+    "fetch_kib": 250096.6, "fetch_scale": 1.9999,
     "write_kib": 14776.0, "write_scale": 1.0,
 }
 
