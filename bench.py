@@ -25,7 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64 = 78.6e12          # MI355X FP64 vector, FLOP/s
-L0_FLOP_PER_SUBSET = 10      # Schur rank-1 extension per 3-subset
+L0_FLOP_PER_SUBSET = 10      # per 3-subset: C' fma 2, t mul 1, den fma 2, e fma 2, e^2 1, bounded test fma 2
 
 # HBM bytes of one k_sweep3 launch on this workload, from rocprofv3 FETCH_SIZE /
 # WRITE_SIZE passes (KiB per dispatch) scaled by what the same counters read for a
@@ -321,8 +321,8 @@ def large_main(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: this build measures the single-GPU path "
-              "(--gpus %d requested); multi-GPU sharding is described in DESIGN.md" % args.gpus)
+        print("bench.py runs on exactly one GPU: the path is measured on a single GPU "
+              "(--gpus %d requested); sharding across GPUs is not implemented" % args.gpus)
         sys.exit(2)
     if args.workload == "batch128":
         return batch_main(args)

@@ -1,7 +1,7 @@
 """GPU parity: the HIP library (through the C ABI) against the FP64 oracle on
 the same seeded inputs.
 
-Bar (see the design doc for the derivation):
+Bar (derived from the FP64 rounding of the two-pass moments and the QR refit):
   * selected candidate IDs, unit-prune counts and L0 winners: identical;
     where the oracle itself has a near-tie (|delta s| <= 1e-12 s at the
     cut, not a duplicate) either member is accepted;
