@@ -18,7 +18,11 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-x", "hip",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
+         "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
+         # kernel arguments arrive in SGPRs at wave start instead of by a
+         # first scalar load (the argument tables' address heads each
+         # kernel's chain of dependent loads)
+         "-mllvm", "-amdgpu-kernarg-preload-count=16"]
 # The Gram kernel's FP64 matrix products keep their accumulators in VGPRs
 # (otherwise they are copied between VGPRs and AGPRs on every chunk).
 EXTRA = {"dsc_l0.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
