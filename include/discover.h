@@ -278,6 +278,16 @@ discover_status discover_sisso_batch(discover_ctx* ctx, const discover_problem* 
                                      int32_t* out_omp_active, double* out_omp_coef,
                                      double* out_omp_rmse, int32_t* out_replayed, void* stream);
 
+/* Initial capacity (entries per problem, >= 1) of the screening's exact
+ * fix-up lists: candidates whose one-pass moments cannot be trusted (a
+ * large mean-to-spread ratio, a sum that may have cancelled) are listed
+ * and decided by the exact two-pass formula.  A screen that lists more
+ * grows the capacity and runs again (in a captured graph the replay's
+ * device-side check fails instead and the call reruns eagerly), so the
+ * value only trades memory for reruns.  Default 4,194,304.
+ * Errors: E_ARG. */
+discover_status discover_set_fixup_capacity(discover_ctx* ctx, int64_t entries);
+
 /* Number of raw candidates |P_R| of a search space (host only). */
 int64_t discover_count(int32_t p, const discover_screen_params* prm);
 

@@ -406,6 +406,168 @@ done:
     return nvalid;
 }
 
+/* Scores of one valid feature against the centered targets, combined as
+ * max_t |r_t| (mode 1: out[id]) or |r_t| per target (mode 0: out[t*N+id]). */
+static void score_feature(int n, const double* f, int T, const double* Yc, const double* syy,
+                          int mode, int64_t N, int64_t id, double* out, double* tmp) {
+    double m, sxx;
+    feature_checks(n, f, tmp, &m, &sxx);
+    double best = 0.0;
+    for (int q = 0; q < T; q++) {
+        double r = fabs(pearson(n, f, m, sxx, Yc + (int64_t)q * n, syy[q], tmp));
+        if (mode == 1) { if (r > best || q == 0) best = r; }
+        else out[(int64_t)q * N + id] = r;
+    }
+    if (mode == 1) out[id] = best;
+}
+
+static void mark_invalid(int T, int mode, int64_t N, int64_t id, double* out) {
+    if (mode == 1) out[id] = NAN;
+    else for (int q = 0; q < T; q++) out[(int64_t)q * N + id] = NAN;
+}
+
+/* Status of a feature f = op(a, b) whose operands have statuses sa, sb and
+ * which is unit-legal: ST_CHILD, or the numerical checks of or_screen. */
+static int derived_status(int o, int n, const double* f, const double* fa, const double* fb,
+                          int sa, int sb, double* tmp) {
+    if (sa != ST_VALID || (fb && sb != ST_VALID)) return ST_CHILD;
+    double m, sxx;
+    int st = feature_checks(n, f, tmp, &m, &sxx);
+    if (st == ST_VALID && fb && cancelled(o, n, f, fa, fb, tmp)) st = ST_CONST;
+    return st;
+}
+
+/* Screening of a space whose top rung R is operator-limited (binary
+ * partners drawn from P_pool with pool <= R-2), without keeping rung R-1 in
+ * memory.  Candidates are taken in a different order than in or_screen but
+ * each one is evaluated, checked and scored by the same routines, so every
+ * score and status is the one or_screen gives:
+ *   - P_{R-2} is evaluated once and kept (values, units, status), and its
+ *     members are scored;
+ *   - for each feature g of rung R-1 with local index j in [j_lo, j_hi):
+ *     g is evaluated from its operands in P_{R-2}, checked and scored; then
+ *     every rung-R candidate with g as its rung-(R-1) operand (unary u(g),
+ *     and op(f_i, g) for i in P_pool) is evaluated, checked and scored.
+ * Candidates of rungs R-1 and R outside the j range are left untouched.
+ *   out     mode 1: [N] max_t |r_t|; mode 0: [T][N] |r_t|; NaN when invalid
+ *   counts  [5] number of visited candidates per ST_* code
+ * Returns 0, or <0 on error (-5: a constant target, -4: the space is not of
+ * this shape). */
+int64_t or_screen_stream(int n, int p, const double* X, int T, const double* Y,
+                         int B, const int32_t* units, int R, const uint32_t* rung_ops,
+                         const int32_t* rung_pool, int64_t N, int mode,
+                         int64_t j_lo, int64_t j_hi, double* out, int64_t* counts) {
+    space_t s;
+    if (space_init(&s, p, R, rung_ops, rung_pool)) return -1;
+    if (N != s.off[R + 1]) return -2;
+    if (R < 2 || s.pool[R] > R - 2) return -4;
+    const int64_t M = s.off[R - 1];             /* |P_{R-2}|: kept */
+    const int64_t L1 = s.L[R - 1];              /* rung R-1: streamed */
+    if (j_lo < 0) j_lo = 0;
+    if (j_hi > L1) j_hi = L1;
+    const int32_t Q = 1 << R;
+    const int Bq = B ? B : 1;
+    double* V = malloc(M * (int64_t)n * 8);
+    int32_t* U = calloc((size_t)(M * Bq), 4);
+    uint8_t* legal = malloc(M); uint8_t* st = malloc(M);
+    double* Yc = malloc((int64_t)T * n * 8); double* syy = malloc(T * 8);
+    double* tmp0 = malloc((int64_t)n * 8);
+    int64_t cnt[5] = {0, 0, 0, 0, 0};
+    int64_t rc = 0;
+    if (prep_targets(n, T, Y, Yc, syy, tmp0)) { rc = -5; goto done; }
+    /* P_{R-2}: values, units, status (operands precede their parents) */
+    for (int64_t t = 0; t < M; t++) {
+        int8_t rg, o; int64_t a, b;
+        or_decode(p, R, s.ops, s.pool, t, &rg, &o, &a, &b);
+        double* f = V + t * n;
+        int32_t* u = U + t * Bq;
+        if (o == OP_NONE) {
+            memcpy(f, X + t * n, (size_t)n * 8);
+            for (int k = 0; k < B; k++) u[k] = units ? units[t * B + k] * Q : 0;
+            legal[t] = 1;
+        } else {
+            apply_op(o, n, V + a * n, b >= 0 ? V + b * n : NULL, f);
+            legal[t] = legal[a] && (b < 0 || legal[b]) &&
+                       unit_rule(o, B, U + a * Bq, b >= 0 ? U + b * Bq : NULL, u);
+            if (!legal[t]) for (int k = 0; k < B; k++) u[k] = 0;
+        }
+        if (!legal[t]) st[t] = ST_UNIT;
+        else if (o == OP_NONE) { double m, sxx; st[t] = (uint8_t)feature_checks(n, f, tmp0, &m, &sxx); }
+        else st[t] = (uint8_t)derived_status(o, n, f, V + a * n, b >= 0 ? V + b * n : NULL,
+                                             st[a], b >= 0 ? st[b] : ST_VALID, tmp0);
+        cnt[st[t]]++;
+        if (st[t] == ST_VALID) score_feature(n, f, T, Yc, syy, mode, N, t, out, tmp0);
+        else mark_invalid(T, mode, N, t, out);
+    }
+    {
+        const int nu = popc(s.ops[R] & 0x1Fu);
+        const int64_t w = s.off[s.pool[R] + 1];       /* partner pool size */
+        #pragma omp parallel
+        {
+            double* g = malloc((int64_t)n * 8); double* f = malloc((int64_t)n * 8);
+            double* tmp = malloc((int64_t)n * 8);
+            int32_t ug[OR_MAXB], uc[OR_MAXB];
+            int64_t lc[5] = {0, 0, 0, 0, 0};
+            #pragma omp for schedule(dynamic, 16)
+            for (int64_t j = j_lo; j < j_hi; j++) {
+                const int64_t gid = s.off[R - 1] + j;
+                int8_t rg, o; int64_t a, b;
+                or_decode(p, R, s.ops, s.pool, gid, &rg, &o, &a, &b);
+                apply_op(o, n, V + a * n, b >= 0 ? V + b * n : NULL, g);
+                int gl = legal[a] && (b < 0 || legal[b]) &&
+                         unit_rule(o, B, U + a * Bq, b >= 0 ? U + b * Bq : NULL, ug);
+                int gs = !gl ? ST_UNIT
+                             : derived_status(o, n, g, V + a * n, b >= 0 ? V + b * n : NULL,
+                                              st[a], b >= 0 ? st[b] : ST_VALID, tmp);
+                lc[gs]++;
+                if (gs == ST_VALID) score_feature(n, g, T, Yc, syy, mode, N, gid, out, tmp);
+                else mark_invalid(T, mode, N, gid, out);
+                /* rung-R children of g, in the order of their IDs */
+                int64_t base = s.off[R];
+                int ui = 0;
+                for (int uo = 0; uo < 5; uo++) {
+                    if (!(s.ops[R] >> uo & 1u)) continue;
+                    const int64_t cid = base + (int64_t)ui * L1 + j;
+                    ui++;
+                    int cs;
+                    if (!gl || !unit_rule(uo, B, ug, NULL, uc)) cs = ST_UNIT;
+                    else {
+                        apply_op(uo, n, g, NULL, f);
+                        cs = derived_status(uo, n, f, g, NULL, gs, ST_VALID, tmp);
+                    }
+                    lc[cs]++;
+                    if (cs == ST_VALID) score_feature(n, f, T, Yc, syy, mode, N, cid, out, tmp);
+                    else mark_invalid(T, mode, N, cid, out);
+                }
+                base += (int64_t)nu * L1;
+                for (int bo = 5; bo < 10; bo++) {
+                    if (!(s.ops[R] >> bo & 1u)) continue;
+                    for (int64_t i = 0; i < w; i++) {
+                        const int64_t cid = base + j * w + i;
+                        int cs;
+                        if (!gl || !legal[i] || !unit_rule(bo, B, U + i * Bq, ug, uc)) cs = ST_UNIT;
+                        else {
+                            apply_op(bo, n, V + i * n, g, f);
+                            cs = derived_status(bo, n, f, V + i * n, g, st[i], gs, tmp);
+                        }
+                        lc[cs]++;
+                        if (cs == ST_VALID) score_feature(n, f, T, Yc, syy, mode, N, cid, out, tmp);
+                        else mark_invalid(T, mode, N, cid, out);
+                    }
+                    base += L1 * w;
+                }
+            }
+            #pragma omp critical
+            for (int k = 0; k < 5; k++) cnt[k] += lc[k];
+            free(g); free(f); free(tmp);
+        }
+    }
+    for (int k = 0; k < 5; k++) counts[k] = cnt[k];
+done:
+    free(V); free(U); free(legal); free(st); free(Yc); free(syy); free(tmp0);
+    return rc;
+}
+
 /* Recursive evaluation of one ID from the primaries, with its status (the
  * same rules as or_screen: unit legality, valid operands, finite values,
  * not constant).  `f` receives n values.  Unit vectors of the operands are
@@ -529,26 +691,28 @@ static int householder_lsq(int n, int m, double* A, double* y, double* coef,
     return 0;
 }
 
-/* Least-squares fit of y on [1, f_1..f_d] (the columns given as pointers).
- * coef[0] is the intercept.  Returns the RSS. */
-double or_lsq(int n, int d, const double* const* cols, const double* y, double* coef) {
+/* Least-squares fit of y on [1, f_1..f_d] (the columns given as pointers)
+ * with caller-provided work space: A n*(d+1), w n.  coef[0] is the
+ * intercept.  Returns the RSS. */
+static double lsq_buf(int n, int d, const double* const* cols, const double* y,
+                      double* coef, double* A, double* w) {
     int m = d + 1;
-    double* A = malloc((int64_t)n * m * 8); double* w = malloc((int64_t)n * 8);
     double rd[16];
     for (int i = 0; i < n; i++) A[i] = 1.0;
     for (int j = 0; j < d; j++) memcpy(A + (int64_t)(j + 1) * n, cols[j], (size_t)n * 8);
     memcpy(w, y, (size_t)n * 8);
     double rss;
     householder_lsq(n, m, A, w, coef, &rss, rd);
-    free(A); free(w);
     return rss;
 }
 
 /* Squared |R_jj| of the QR of the centered, unit-norm columns (in the given
- * order): the Cholesky pivots of their correlation matrix. */
-void or_pivots(int n, int d, const double* const* cols, double* piv) {
-    double* A = malloc((int64_t)n * d * 8); double* w = calloc(n, 8);
+ * order): the Cholesky pivots of their correlation matrix.  Work space:
+ * A n*d, w n. */
+static void pivots_buf(int n, int d, const double* const* cols, double* piv,
+                       double* A, double* w) {
     double coef[16], rd[16], rss;
+    for (int i = 0; i < n; i++) w[i] = 0.0;
     for (int j = 0; j < d; j++) {
         double* c = A + (int64_t)j * n;
         memcpy(c, cols[j], (size_t)n * 8);
@@ -561,6 +725,18 @@ void or_pivots(int n, int d, const double* const* cols, double* piv) {
     }
     householder_lsq(n, d, A, w, coef, &rss, rd);
     for (int j = 0; j < d; j++) piv[j] = rd[j] * rd[j];
+}
+
+double or_lsq(int n, int d, const double* const* cols, const double* y, double* coef) {
+    double* A = malloc((int64_t)n * (d + 1) * 8); double* w = malloc((int64_t)n * 8);
+    double rss = lsq_buf(n, d, cols, y, coef, A, w);
+    free(A); free(w);
+    return rss;
+}
+
+void or_pivots(int n, int d, const double* const* cols, double* piv) {
+    double* A = malloc((int64_t)n * d * 8); double* w = malloc((int64_t)n * 8);
+    pivots_buf(n, d, cols, piv, A, w);
     free(A); free(w);
 }
 
@@ -574,42 +750,71 @@ static int next_comb(int* c, int D, int S) {
     return 1;
 }
 
+static int64_t binom(int64_t a, int64_t b) {
+    if (b < 0 || a < b) return 0;
+    int64_t r = 1;
+    for (int64_t z = 0; z < b; z++) r = r * (a - z) / (z + 1);
+    return r;
+}
+
+/* RSS of one subset by QR with an intercept (Eq. (1)), or NaN when its
+ * smallest normalized pivot is <= piv_tol.  Work space A n*(D+1), w n. */
+static double subset_rss(int n, const double* F, const double* y, int D, const int* sub,
+                         double piv_tol, double* A, double* w) {
+    const double* cols[8]; double coef[9], piv[8];
+    for (int k = 0; k < D; k++) cols[k] = F + (int64_t)sub[k] * n;
+    pivots_buf(n, D, cols, piv, A, w);
+    double mn = piv[0];
+    for (int k = 1; k < D; k++) if (piv[k] < mn) mn = piv[k];
+    return (mn > piv_tol) ? lsq_buf(n, D, cols, y, coef, A, w) : NAN;
+}
+
 /* Direct mode: every D-subset of the S rows of F ([S][n]) in lexicographic
  * order is fitted by Householder QR with an intercept.  rss[t] is NaN when
- * the subset's smallest pivot (see or_pivots) is <= piv_tol.  Returns the
- * number of subsets. */
+ * the subset's smallest pivot (see or_pivots) is <= piv_tol.  The subsets
+ * with first element a occupy the C(S-1-a, D-1) positions after those of
+ * a-1; each thread walks the subsets of one a in order.  Returns the number
+ * of subsets. */
 int64_t or_l0_direct(int n, int S, const double* F, const double* y, int D,
                      double piv_tol, double* rss) {
     if (D < 1 || D > 8 || S < D) return 0;
-    int64_t total = 0;
-    int c[8];
-    for (int k = 0; k < D; k++) c[k] = k;
-    do { total++; } while (next_comb(c, D, S));
+    const int64_t total = binom(S, D);
+    int64_t* start = malloc((size_t)(S + 1) * 8);
+    start[0] = 0;
+    for (int a = 0; a < S; a++) start[a + 1] = start[a] + binom(S - 1 - a, D - 1);
     #pragma omp parallel
     {
-        int cc[8]; const double* cols[8]; double coef[9], piv[8];
-        #pragma omp for schedule(dynamic, 64)
-        for (int64_t t = 0; t < total; t++) {
-            /* unrank t by stepping from the start (plain, slow) */
-            int64_t rem = t; int lo = 0;
-            for (int k = 0; k < D; k++) {
-                for (int v = lo;; v++) {
-                    /* number of subsets with cc[k] = v: C(S-1-v, D-1-k) */
-                    int64_t cnt = 1; int nn = S - 1 - v, kk = D - 1 - k;
-                    for (int z = 0; z < kk; z++) cnt = cnt * (nn - z) / (z + 1);
-                    if (nn < kk) cnt = 0;
-                    if (rem < cnt) { cc[k] = v; lo = v + 1; break; }
-                    rem -= cnt;
-                }
-            }
-            for (int k = 0; k < D; k++) cols[k] = F + (int64_t)cc[k] * n;
-            or_pivots(n, D, cols, piv);
-            double mn = piv[0];
-            for (int k = 1; k < D; k++) if (piv[k] < mn) mn = piv[k];
-            rss[t] = (mn > piv_tol) ? or_lsq(n, D, cols, y, coef) : NAN;
+        double* A = malloc((int64_t)n * (D + 1) * 8); double* w = malloc((int64_t)n * 8);
+        int cc[8];
+        #pragma omp for schedule(dynamic, 1)
+        for (int a = 0; a <= S - D; a++) {
+            for (int k = 0; k < D; k++) cc[k] = a + k;
+            int64_t t = start[a];
+            do {
+                rss[t++] = subset_rss(n, F, y, D, cc, piv_tol, A, w);
+            } while (next_comb(cc, D, S) && cc[0] == a);
         }
+        free(A); free(w);
     }
+    free(start);
     return total;
+}
+
+/* RSS by QR (as in direct mode) of a list of D-subsets: sub [count][D]
+ * positions into F ([S][n]); rss [count], NaN for singular subsets. */
+void or_l0_subsets(int n, const double* F, const double* y, int D, int64_t count,
+                   const int32_t* sub, double piv_tol, double* rss) {
+    #pragma omp parallel
+    {
+        double* A = malloc((int64_t)n * (D + 1) * 8); double* w = malloc((int64_t)n * 8);
+        int cc[8];
+        #pragma omp for schedule(dynamic, 16)
+        for (int64_t t = 0; t < count; t++) {
+            for (int k = 0; k < D; k++) cc[k] = sub[t * D + k];
+            rss[t] = subset_rss(n, F, y, D, cc, piv_tol, A, w);
+        }
+        free(A); free(w);
+    }
 }
 
 /* Correlation matrix of the centered, unit-norm rows of F ([S][n]) and
@@ -656,16 +861,19 @@ void or_corr_matrix(int n, int S, const double* F, const double* y, double* C,
 /* Explained fraction q = c_S^T C_SS^{-1} c_S of one subset by Cholesky of
  * the D x D correlation block in subset order; the pivots are the
  * squared diagonal of the Cholesky factor.  Returns 0 when any pivot is
- * <= piv_tol (rank-deficient), 1 otherwise. */
+ * <= piv_tol (rank-deficient), 1 otherwise; *pmin receives the smallest
+ * pivot. */
 static int gram_subset(int S, const double* C, const double* c, int D, const int* sub,
-                       double piv_tol, double* q) {
+                       double piv_tol, double* q, double* pmin) {
     double L[8][8], z[8];
+    double mn = 1.0;
     for (int i = 0; i < D; i++) {
         for (int j = 0; j <= i; j++) {
             double acc = C[(int64_t)sub[i] * S + sub[j]];
             for (int k = 0; k < j; k++) acc -= L[i][k] * L[j][k];
             if (i == j) {
                 if (!(acc > piv_tol)) return 0;
+                if (acc < mn) mn = acc;
                 L[i][i] = sqrt(acc);
             } else {
                 L[i][j] = acc / L[j][j];
@@ -680,14 +888,23 @@ static int gram_subset(int S, const double* C, const double* c, int D, const int
         acc2 += z[i] * z[i];
     }
     *q = acc2;
+    *pmin = mn;
     return 1;
+}
+
+/* Rounding allowance of a Gram-route explained fraction: the correlation
+ * entries carry errors of a few ulps, which the solve amplifies by the
+ * condition number of the block, about D / (smallest pivot). */
+static double gram_slack(int D, double pmin) {
+    return 64.0 * D * 2.220446049250313e-16 / pmin;
 }
 
 /* Gram mode, used where fitting every subset by QR is too slow: the
  * explained fraction of each D-subset from the correlation matrix
  * (mathematically RSS = yy (1 - q)).  Pass 1 finds the m-th largest q over
  * all non-singular subsets; pass 2 returns every subset with
- * q >= q_(m) - delta (the band that is then refitted by QR).
+ * q >= q_(m) - delta - (its rounding allowance, which grows as its smallest
+ * pivot shrinks): the band that is then refitted by QR.
  *   band  [cap][D] positions (ascending), bq [cap]
  * Returns the band size (which may exceed cap: then only cap are written),
  * or -1 if fewer than one non-singular subset exists. */
@@ -705,8 +922,8 @@ int64_t or_l0_gram_band(int S, const double* C, const double* c, int D,
             sub[0] = a;
             for (int k = 1; k < D; k++) sub[k] = a + k;
             do {
-                double q;
-                if (gram_subset(S, C, c, D, sub, piv_tol, &q)) {
+                double q, pm;
+                if (gram_subset(S, C, c, D, sub, piv_tol, &q, &pm)) {
                     if (ln < m || q > lb[ln - 1]) {   /* keep top-m, descending */
                         int pos = ln < m ? ln++ : m - 1;
                         while (pos > 0 && lb[pos - 1] < q) { lb[pos] = lb[pos - 1]; pos--; }
@@ -744,8 +961,9 @@ int64_t or_l0_gram_band(int S, const double* C, const double* c, int D,
             sub[0] = a;
             for (int k = 1; k < D; k++) sub[k] = a + k;
             do {
-                double q;
-                if (gram_subset(S, C, c, D, sub, piv_tol, &q) && q >= thr) {
+                double q, pm;
+                if (gram_subset(S, C, c, D, sub, piv_tol, &q, &pm) &&
+                    q >= thr - gram_slack(D, pm)) {
                     int64_t slot;
                     #pragma omp atomic capture
                     slot = count++;

@@ -51,6 +51,7 @@ TAU_DUP = 1e-9      # 1 - |corr| below which two features are duplicates
 PIV_TOL = 1e-10     # normalized Cholesky pivot at or below which a subset is singular
 GRAM_DELTA = 1e-7   # band (explained fraction) refitted by QR after the Gram scan
 TAU_TIE = 1e-11     # RSS tie tolerance relative to ||y - mean||^2
+DIRECT_MAX = 4_000_000   # "auto" L0 fits every subset by QR up to this many subsets
 
 
 def build(force=False):
@@ -96,6 +97,12 @@ def lib():
         L.or_pivots.argtypes = [C.c_int, C.c_int, P, P]
         L.or_l0_direct.restype = C.c_int64
         L.or_l0_direct.argtypes = [C.c_int, C.c_int, P, P, C.c_int, C.c_double, P]
+        L.or_l0_subsets.restype = None
+        L.or_l0_subsets.argtypes = [C.c_int, P, P, C.c_int, C.c_int64, P, C.c_double, P]
+        L.or_screen_stream.restype = C.c_int64
+        L.or_screen_stream.argtypes = [C.c_int, C.c_int, P, C.c_int, P, C.c_int, P,
+                                       C.c_int, P, P, C.c_int64, C.c_int, C.c_int64,
+                                       C.c_int64, P, P]
         L.or_corr_matrix.restype = None
         L.or_corr_matrix.argtypes = [C.c_int, C.c_int, P, P, P, P, P]
         L.or_l0_gram_band.restype = C.c_int64
@@ -144,6 +151,17 @@ class Space:
                                     _p(self.levels)))
         if self.N < 0:
             raise ValueError("invalid search space")
+
+    @property
+    def streamable(self):
+        """True when the top rung is operator-limited with partners from
+        P_pool, pool <= R-2 (its rung R-1 operand can be streamed)."""
+        return self.R >= 2 and 0 <= int(self.pools[self.R]) <= self.R - 2
+
+    @property
+    def rung_start(self):
+        """ID of the first candidate of each rung 0..R, and N."""
+        return np.concatenate([[0], np.cumsum(self.levels)]).astype(np.int64)
 
     @classmethod
     def of(cls, w):
@@ -215,6 +233,43 @@ def screen_all(space, X, Y, units):
     return scores, status, int(nv)
 
 
+STREAM_BYTES = 2 << 30   # score arrays larger than this are screened by streaming
+
+
+def screen_scores(space, X, Y, units, mode, j_range=None):
+    """Combined screening scores of every raw candidate: [T'][N] with
+    T' = 1 (mode "max": max_t |r_t|) or T (|r_t| per target), NaN when
+    invalid; the number of valid candidates; the per-candidate status
+    (None when streamed); the count of each status code.  Spaces whose top rung is
+    operator-limited are screened by streaming their rung R-1 operand
+    (same arithmetic, no [T][N] array of signed r); ``j_range`` then
+    restricts the streamed rung-(R-1) features (a timing sample; the other
+    entries of those rungs stay NaN)."""
+    X = np.ascontiguousarray(X, np.float64)
+    Y = np.ascontiguousarray(np.atleast_2d(Y), np.float64)
+    T, n = Y.shape
+    big = space.N * T * 8 > STREAM_BYTES
+    if not space.streamable or (not big and j_range is None):
+        r, status, nvalid = screen_all(space, X, Y, units)
+        counts = np.bincount(status, minlength=5)[:5].astype(np.int64)
+        return combine_scores(r, mode), int(nvalid), status, counts
+    B = 0 if units is None else units.shape[1]
+    uin = None if units is None else np.ascontiguousarray(units, np.int32)
+    Tp = 1 if mode == "max" else T
+    out = np.full((Tp, space.N), np.nan, np.float64)
+    counts = np.zeros(5, np.int64)
+    lo, hi = (0, int(space.levels[space.R - 1])) if j_range is None else j_range
+    rc = lib().or_screen_stream(n, space.p, _p(X), T, _p(Y), B, _p(uin), space.R,
+                                _p(space.masks), _p(space.pools), space.N,
+                                1 if mode == "max" else 0, int(lo), int(hi),
+                                _p(out), _p(counts))
+    if rc == -5:
+        raise ValueError("constant target")
+    if rc < 0:
+        raise RuntimeError("or_screen_stream failed (%d)" % rc)
+    return out, int(counts[ST_VALID]), None, counts
+
+
 def values(space, X, units, ids):
     """Values [m][n] and status [m] of candidate IDs, evaluated recursively
     from the primaries."""
@@ -260,13 +315,35 @@ def _corr_abs(u, v):
 
 def select(score, k, exclude=(), dedup=True, value_fn=None):
     """Exact top-k of one score vector (index = candidate ID; NaN = invalid)
-    with the duplicate-group rule.  Returns (ids, scores) of the selected
-    group representatives in (-score, ID) order, and the scan record
-    (groups formed, duplicates merged)."""
+    with the duplicate-group rule.  A score of exactly 0 (a candidate with no
+    linear association with the target) is never selected.  Returns (ids,
+    scores) of the selected group representatives in (-score, ID) order, and
+    the scan record (groups formed, duplicates merged)."""
     score = np.asarray(score, np.float64)
-    valid = np.nonzero(~np.isnan(score))[0]
-    order = valid[np.lexsort((valid, -score[valid]))]       # (-s, ID)
+    valid = np.nonzero(score > 0)[0]          # NaN and exact zeros drop out
     excl = set(int(e) for e in exclude)
+    # The scan visits candidates in (-s, ID) order and stops early.  For a
+    # long vector, sort only the candidates above the K-th largest score
+    # (strictly, so the kept set does not depend on how ties are split),
+    # and accept the scan if it stopped inside them; otherwise keep more.
+    keep = 16 * (k + len(excl)) + 4096
+    while True:
+        if len(valid) > 4 * keep:
+            sv = score[valid]
+            thr = np.partition(sv, len(sv) - keep)[len(sv) - keep]
+            cand = valid[sv > thr]
+            complete = False
+        else:
+            cand = valid
+            complete = True
+        order = cand[np.lexsort((cand, -score[cand]))]       # (-s, ID)
+        res = _scan(score, order, k, excl, dedup, value_fn)
+        if complete or res[3]:
+            return res[:3]
+        keep *= 8
+
+
+def _scan(score, order, k, excl, dedup, value_fn):
     heads, members, blocked = [], [], []          # per group
     vals = {}
 
@@ -285,11 +362,13 @@ def select(score, k, exclude=(), dedup=True, value_fn=None):
         return None
 
     n_merged = 0
+    stopped = False
     for c in order:
         c = int(c)
         sc = score[c]
         lim = kth_unblocked_head_score()
         if lim is not None and sc < (1.0 - TAU_NEAR) * lim:
+            stopped = True
             break
         grp = -1
         if dedup:
@@ -317,14 +396,16 @@ def select(score, k, exclude=(), dedup=True, value_fn=None):
     reps = np.array(reps, np.int64)
     sc = score[reps] if len(reps) else np.zeros(0)
     o = np.lexsort((reps, -sc))
-    return reps[o], sc[o], {"groups": len(heads), "merged": n_merged}
+    return reps[o], sc[o], {"groups": len(heads), "merged": n_merged}, stopped
 
 
 def sis(space, X, units, targets, k, exclude=(), mode="per_target", dedup=True):
     """Screen every candidate against the targets and select the top-k
-    (per target, or one list scored by the maximum over targets)."""
-    r, status, nvalid = screen_all(space, X, targets, units)
-    sc = combine_scores(r, mode)
+    (per target, or one list scored by the maximum over targets).  Returns
+    (one (ids, scores, record) per list, status, number of valid
+    candidates); status is the per-candidate ST_* array, or, when the space
+    was streamed, the count of each ST_* code."""
+    sc, nvalid, status, counts = screen_scores(space, X, targets, units, mode)
     cache = {}
 
     def value_fn(cid):
@@ -333,6 +414,8 @@ def sis(space, X, units, targets, k, exclude=(), mode="per_target", dedup=True):
         return cache[cid]
 
     out = [select(sc[t], k, exclude, dedup, value_fn) for t in range(sc.shape[0])]
+    if status is None:
+        status = counts
     return out, status, nvalid
 
 
@@ -390,12 +473,44 @@ def all_subsets(S, D):
     return list(itertools.combinations(range(S), D))
 
 
+def unrank(t, S, D):
+    """The t-th D-subset of range(S) in lexicographic order."""
+    out, lo = [], 0
+    for k in range(D):
+        v = lo
+        while True:
+            cnt = math.comb(S - 1 - v, D - 1 - k)
+            if t < cnt:
+                break
+            t -= cnt
+            v += 1
+        out.append(v)
+        lo = v + 1
+    return tuple(out)
+
+
+def subset_rss(F, y, subsets):
+    """RSS by QR with an intercept of each subset (rows [count][D] of
+    positions into F); NaN when a normalized pivot is <= PIV_TOL."""
+    F = np.ascontiguousarray(F, np.float64)
+    y = np.ascontiguousarray(y, np.float64)
+    sub = np.ascontiguousarray(np.atleast_2d(subsets), np.int32)
+    rss = np.empty(sub.shape[0], np.float64)
+    if sub.shape[0]:
+        lib().or_l0_subsets(F.shape[1], _p(F), _p(y), sub.shape[1], sub.shape[0],
+                            _p(sub), PIV_TOL, _p(rss))
+    return rss
+
+
 def l0(F, ids, y, D, m=1, mode="auto"):
     """Exhaustive L0 over every D-subset of the rows of F (Eq. (1) with an
     intercept).  mode "direct" fits every subset by QR; "gram" scans the
     explained fraction from the correlation matrix and refits the band
-    within GRAM_DELTA of the m-th best by QR.  Returns a list of m models:
-    dicts with positions, ids, rss, rmse, coef, resid."""
+    within GRAM_DELTA of the m-th best by QR (a shortcut for subset counts
+    where QR of every subset takes hours; its agreement with direct mode is
+    checked by the test suite and by the reference-building script); "auto"
+    is direct up to DIRECT_MAX subsets.  Returns a list of m models: dicts
+    with positions, ids, rss, rmse, coef, resid."""
     F = np.ascontiguousarray(F, np.float64)
     y = np.ascontiguousarray(y, np.float64)
     S, n = F.shape
@@ -403,15 +518,20 @@ def l0(F, ids, y, D, m=1, mode="auto"):
     yc = y - y.mean()
     yy = float(np.dot(yc, yc))
     if mode == "auto":
-        mode = "direct" if math.comb(S, D) <= 20000 else "gram"
+        mode = "direct" if math.comb(S, D) <= DIRECT_MAX else "gram"
     cands = []
     if mode == "direct":
         tot = math.comb(S, D)
         rss = np.empty(tot, np.float64)
         got = lib().or_l0_direct(n, S, _p(F), _p(y), D, PIV_TOL, _p(rss))
         assert got == tot
-        for t, sub in enumerate(all_subsets(S, D)):
-            if not np.isnan(rss[t]):
+        # Every model the ranking below can pick has an RSS within TAU_TIE * yy
+        # of the m-th smallest RSS, so only those subsets are ranked.
+        fin = rss[~np.isnan(rss)]
+        if len(fin):
+            mth = np.partition(fin, min(m, len(fin)) - 1)[min(m, len(fin)) - 1]
+            for t in np.nonzero(rss <= mth + TAU_TIE * yy)[0]:
+                sub = unrank(int(t), S, D)
                 cands.append((float(rss[t]), tuple(sorted(int(ids[i]) for i in sub)), sub))
     else:
         Cm, c, _ = corr_matrix(F, y)

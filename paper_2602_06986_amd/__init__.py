@@ -67,7 +67,7 @@ class L0Stats(C.Structure):
 SYMBOLS = ("discover_create", "discover_destroy", "discover_last_error",
            "discover_generate_screen", "discover_l0_fit", "discover_omp", "discover_count",
            "discover_decode", "discover_set_timing", "discover_timing", "discover_reset_timing",
-           "discover_sisso_batch", "discover_set_graph_timing")
+           "discover_sisso_batch", "discover_set_graph_timing", "discover_set_fixup_capacity")
 
 _lib = None
 
@@ -102,6 +102,7 @@ def lib():
                                            C.c_int32, C.c_int32, C.c_int32, P, P, P, P, P,
                                            C.c_int32, P, P, P, C.POINTER(C.c_int32), P]
         L.discover_set_graph_timing.argtypes = [P, C.c_char_p]
+        L.discover_set_fixup_capacity.argtypes = [P, C.c_int64]
         _lib = L
     return _lib
 
@@ -180,6 +181,10 @@ class Context:
 
     def reset_timing(self):
         _check(lib().discover_reset_timing(self.h))
+
+    def set_fixup_capacity(self, entries):
+        """Initial entries of the screening's exact fix-up lists."""
+        _check(lib().discover_set_fixup_capacity(self.h, int(entries)))
 
     def timing(self, kernel):
         n = C.c_int64()

@@ -103,6 +103,15 @@ extern "C" discover_status discover_decode(int32_t p, const discover_screen_para
     });
 }
 
+extern "C" discover_status discover_set_fixup_capacity(discover_ctx* ctx, int64_t entries) {
+    using namespace dsc;
+    return guarded([&] {
+        DSC_REQUIRE(ctx, "ctx is NULL");
+        DSC_REQUIRE(entries >= 1, "fix-up capacity must be >= 1");
+        ctx->fix_cap_min = entries;
+    });
+}
+
 extern "C" discover_status discover_set_timing(discover_ctx* ctx, int32_t enable) {
     using namespace dsc;
     return guarded([&] {

@@ -25,7 +25,8 @@ __global__ __launch_bounds__(256) void k_verdict(ctab<ListCheck> L, int nl, ctab
         DSC_GLOBAL(c.res); DSC_GLOBAL(c.ctr);
         const int64_t* r = c.res;
         bad = r[4] > c.cap || (c.dedup && r[3] > c.fcap) || !(r[1] || c.K >= c.N) ||
-              (c.ctr[0] & 0xFFFFFFFFull) != 0;
+              (c.ctr[0] & 0xFFFFFFFFull) != 0 ||
+              (int64_t)c.ctr[1] > c.fix_cap || (int64_t)c.ctr[3] > c.fix_cap;
     } else if (i < nl + nbc) {
         const BandCheck& c = tab(B, i - nl);
         DSC_GLOBAL(c.cnt);

@@ -126,6 +126,10 @@ struct discover_ctx {
     // released (a buffer regrown, plans evicted); graphs of an older
     // generation are discarded instead of replayed.
     uint64_t generation = 0;
+    // Entries of a screen's exact fix-up lists (candidates whose one-pass
+    // score is not trusted); a screen that needs more grows this and runs
+    // again.
+    int64_t fix_cap_min = (int64_t)1 << 22;
     hipStream_t side = nullptr;            // private stream for uploads during capture
 
     // Grow-only named device buffer of at least `bytes` bytes.

@@ -25,6 +25,7 @@ struct ListCheck {
     int64_t cap, fcap, K, N;
     const unsigned long long* ctr;
     int dedup;
+    int64_t fix_cap;          // entries of the problem's two fix-up lists (ctr[1], ctr[3])
 };
 
 // Where the models of one L0 problem go: model q at sub + q * sub_ld (D row

@@ -2734,7 +2734,7 @@ static void layout_problems(discover_ctx* ctx, const discover_problem* probs, in
         P.ldm = pl.ldm;
         P.Mc = sp.Mc();
         P.N = sp.n_raw();
-        P.fix_cap = std::min<int64_t>(P.N, (int64_t)1 << 22);
+        P.fix_cap = std::min<int64_t>(P.N, ctx->fix_cap_min);
         P.pairs = sp.streamed && (pl.dense_ops || pl.list_ops);
         const size_t Mc = P.Mc, ldn = P.ldn, n = P.n, ldm = P.ldm;
         auto& v = o[b];
@@ -3314,10 +3314,14 @@ static std::string call_key(const discover_problem* probs, int nb, const discove
     return k;
 }
 
-void generate_screen(discover_ctx* ctx, const discover_problem* probs, int nb,
-                     const discover_screen_params& prm, const std::vector<ScreenOut>& outs,
-                     discover_screen_stats* out_stats, hipStream_t st, std::vector<ListCheck>* checks,
-                     const std::vector<FillSeg>* extra_fills) {
+struct FixRegrow {
+    int64_t need;
+};
+
+static void generate_screen_once(discover_ctx* ctx, const discover_problem* probs, int nb,
+                                 const discover_screen_params& prm, const std::vector<ScreenOut>& outs,
+                                 discover_screen_stats* out_stats, hipStream_t st,
+                                 std::vector<ListCheck>* checks, const std::vector<FillSeg>* extra_fills) {
     std::vector<Problem> PS;
     std::vector<ListState> LS;
     std::vector<int> act;
@@ -3382,7 +3386,7 @@ void generate_screen(discover_ctx* ctx, const discover_problem* probs, int nb,
                 for (size_t q = 0; q < act.size(); q++) {
                     const ListState& L = LS[act[q]];
                     checks->push_back(ListCheck{sa[q].res, L.cap, L.fcap, L.K, PS[L.b].N,
-                                                PS[L.b].ctr, prm.dedup});
+                                                PS[L.b].ctr, prm.dedup, PS[L.b].fix_cap});
                 }
             break;
         }
@@ -3400,11 +3404,18 @@ void generate_screen(discover_ctx* ctx, const discover_problem* probs, int nb,
                 DSC_HIP(hipMemcpyAsync(&h_ctr[4 * b], PS[b].ctr, 32, hipMemcpyDeviceToHost, st));
         DSC_HIP(hipStreamSynchronize(st));
         if (!checked_bad) {
+            int64_t need = 0;
             for (int b = 0; b < nb; b++) {
                 if ((int)(h_ctr[4 * b] & 0xFFFFFFFFull))
                     DSC_FAIL(DISCOVER_E_NUMERIC, "problem %d: a target column is constant or not finite", b);
                 stats[b].n_scored = (int64_t)h_ctr[4 * b + 2];
+                const int64_t nf = (int64_t)std::max(h_ctr[4 * b + 1], h_ctr[4 * b + 3]);
+                if (nf > PS[b].fix_cap) need = std::max(need, nf);
             }
+            // a fix-up list overflowed: candidates past its end were neither
+            // scored nor rescored, so the whole screen runs again with room
+            // for every one of them
+            if (need) throw FixRegrow{need};
             checked_bad = true;
         }
         std::vector<int> next;
@@ -3481,6 +3492,22 @@ void generate_screen(discover_ctx* ctx, const discover_problem* probs, int nb,
         ctx->resolve_timing();
         if (out_stats)
             for (int b = 0; b < nb; b++) out_stats[b] = stats[b];
+    }
+}
+
+void generate_screen(discover_ctx* ctx, const discover_problem* probs, int nb,
+                     const discover_screen_params& prm, const std::vector<ScreenOut>& outs,
+                     discover_screen_stats* out_stats, hipStream_t st, std::vector<ListCheck>* checks,
+                     const std::vector<FillSeg>* extra_fills) {
+    for (;;) {
+        try {
+            generate_screen_once(ctx, probs, nb, prm, outs, out_stats, st, checks, extra_fills);
+            return;
+        } catch (const FixRegrow& r) {
+            if (r.need >= ((int64_t)1 << 40))
+                DSC_FAIL(DISCOVER_E_CAPACITY, "fix-up list of %lld entries", (long long)r.need);
+            ctx->fix_cap_min = r.need + r.need / 4 + 4096;
+        }
     }
 }
 

@@ -428,3 +428,77 @@ def test_screen_rung3_limited(torch, ctx, D, oracle_mod, seed, p, n, B, T, mode)
     assert st["n_scored"] == nvalid
     V, _ = O.values(sp, X, units, ids[0].cpu().numpy())
     np.testing.assert_allclose(vals[0].cpu().numpy(), V, rtol=1e-12, atol=0)
+
+
+# ------------------------------------------------ degenerate inputs
+def _degenerate_X(rng, p, n):
+    """Primaries that exercise every validity path: negatives (log and sqrt
+    of values <= 0), exact zeros (division by zero, log 0), magnitudes whose
+    exp overflows, a constant offset far above the spread (large
+    mean-to-spread ratio: the one-pass moments are not trusted and the exact
+    fix-up decides), a NaN (every candidate built on that column is
+    invalid) and an affine copy of another column (duplicate groups)."""
+    X = rng.lognormal(0, 0.5, size=(p, n))
+    X[1] -= 1.0
+    X[2, ::7] = 0.0
+    X[3] *= 400.0
+    X[4] = 1000.0 + rng.uniform(0.0, 1.0, size=n)
+    X[5, 5] = np.nan
+    if p > 6:
+        X[6] = 2.0 * X[0] + 1.0
+    return X
+
+
+@pytest.mark.parametrize("seed,p,n,R,fixcap", [(0, 7, 64, 2, 0), (1, 7, 130, 2, 3),
+                                              (2, 6, 45, 3, 0), (3, 6, 70, 3, 5)])
+def test_screen_degenerate_inputs(torch, ctx, D, oracle_mod, seed, p, n, R, fixcap):
+    """Non-finite and degenerate candidates are pruned exactly as the oracle
+    prunes them (counts of unit-valid and scored candidates equal), and the
+    selection matches.  With a tiny fix-up capacity the screen overflows its
+    fix-up list, grows it and runs again with the same result."""
+    import synth
+    O = oracle_mod
+    rng = np.random.default_rng(500 + seed)
+    X = _degenerate_X(rng, p, n)
+    y = X[0] * np.abs(X[1]) + 0.5 * np.exp(-X[0]) + 0.01 * rng.normal(size=n)
+    if R == 3:
+        sp = O.Space(p, 3, O.OPS, rung_ops=(None, None, None, synth.BINARY_OPS),
+                     rung_pool=(None, None, None, 0))
+        prm = D.params(rung=3, k=30, rung_ops=(None, None, None, synth.BINARY_OPS),
+                       rung_pool=(None, None, None, 0))
+    else:
+        sp = O.Space(p, R, O.OPS)
+        prm = D.params(rung=R, k=30)
+    (lst,), status, nvalid = O.sis(sp, X, None, y[None], 30, (), "per_target", True)
+    counts = status if len(status) == 5 else np.bincount(status, minlength=5)
+    assert counts[O.ST_NONFINITE] > 0 and counts[O.ST_CONST] >= 0 and counts[O.ST_CHILD] > 0
+    if fixcap:
+        ctx.set_fixup_capacity(fixcap)
+    try:
+        ids, sc, vals, st = ctx.generate_screen(dev(torch, X), dev(torch, y[None]), prm)
+    finally:
+        if fixcap:
+            ctx.set_fixup_capacity(1 << 22)
+    check_selection(ids[0].cpu().numpy(), sc[0].cpu().numpy(), lst[0], lst[1],
+                    what="degenerate seed %d" % seed)
+    assert st["n_unit_valid"] == sp.N - int(counts[O.ST_UNIT])
+    assert st["n_scored"] == nvalid, (st["n_scored"], nvalid)
+    n_sel = int((ids[0] >= 0).sum())
+    V, vst = O.values(sp, X, None, ids[0][:n_sel].cpu().numpy())
+    assert bool((vst == 0).all())
+    np.testing.assert_allclose(vals[0][:n_sel].cpu().numpy(), V, rtol=1e-10,
+                               atol=1e-14 * float(np.max(np.abs(V))))
+
+
+def test_sisso_degenerate_inputs(torch, ctx, D, oracle_mod):
+    """The whole loop (screen, L0 D <= 2, residuals) on the degenerate
+    primaries, rung 2."""
+    O = oracle_mod
+    rng = np.random.default_rng(600)
+    X = _degenerate_X(rng, 7, 90)
+    y = 1.5 * X[0] * X[3] / 400.0 - 0.7 * np.exp(-X[0]) + 1e-3 * rng.normal(size=90)
+    w = {"name": "degenerate", "X": X, "Y": y[None], "units": None, "p": 7, "n": 90, "T": 1,
+         "B": 0, "ops": O.OPS, "rung": 2, "rung_ops": None, "rung_pool": None, "k": 15, "D": 2,
+         "score_mode": "per_target", "n_resid": 1, "omp_D": 0}
+    ref, got = run_both(torch, ctx, D, O, w)
+    compare_sisso(ref, got, w, "degenerate")
