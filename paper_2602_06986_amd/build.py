@@ -12,7 +12,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdiscover.so")
-SOURCES = ["dsc_abi.cpp", "dsc_space.cpp", "dsc_screen.hip", "dsc_l0.hip", "dsc_batch.hip"]
+SOURCES = ["dsc_abi.cpp", "dsc_space.cpp", "dsc_screen.hip", "dsc_r3.hip", "dsc_l0.hip", "dsc_batch.hip"]
 ARCH = os.environ.get("DISCOVER_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -23,9 +23,11 @@ FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-x", "hip",
          # first scalar load (the argument tables' address heads each
          # kernel's chain of dependent loads)
          "-mllvm", "-amdgpu-kernarg-preload-count=16"]
-# The Gram kernel's FP64 matrix products keep their accumulators in VGPRs
-# (otherwise they are copied between VGPRs and AGPRs on every chunk).
-EXTRA = {"dsc_l0.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
+# The FP64 matrix products of the Gram and rung-3 kernels keep their
+# accumulators in VGPRs (otherwise they are copied between VGPRs and AGPRs
+# on every chunk).
+EXTRA = {"dsc_l0.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
+         "dsc_r3.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
 
 
 def _obj(src):

@@ -1,0 +1,82 @@
+// Operator-limited rung 3 (binary operators, partner from a materialised
+// rung, second operand a rung-2 feature regenerated on the fly): the plan
+// of its work lists and the launch of its screening kernels.
+//
+// The products mul / div / rdiv of a partner x with a rung-2 feature g have
+// moments that are sums of products over samples:
+//   S1 = sum x g,  S2 = sum x^2 g^2,  P_t = sum (x y_t) g      (mul)
+// and the same with h = 1/g (div) or w = 1/x (rdiv).  For a block of 16
+// rung-2 features and 16 partner columns these are 16 x 16 matrix products
+// over samples, computed on the FP64 matrix cores; add / sub (same-unit
+// pairs only when units are given) run on the vector units.
+#pragma once
+
+#include <algorithm>
+#include <memory>
+#include <vector>
+
+#include "dsc_space.h"
+
+namespace dsc {
+
+struct R3Plan {
+    // every unit-legal rung-2 feature, in ID order: x = k (compact operand,
+    // -1 for a unary operator), y = l | op2 << 28
+    int2* grec = nullptr;
+    int64_t n_grec = 0;
+    // partner columns, 16 per tile: partner | kind << 16 (kind 0 mul, 1 rdiv:
+    // tiles against g; kind 2 div: tiles against 1/g), -1 for padding
+    int32_t* coldesc = nullptr;
+    int n_ctiles = 0, n_gct = 0;      // tiles; the first n_gct multiply g
+    std::vector<int32_t> h_coldesc;
+    // add / sub over same-unit pairs: the records whose unit vector some
+    // partner shares, grouped by unit vector and operator (runs padded to
+    // 16); per unit vector, column tiles of up to 15 such partners plus a
+    // column of ones (column 15); one wave per (row tile, column tile)
+    int2* as_grec = nullptr;
+    int64_t n_as_grec = 0;
+    int32_t* as_coldesc = nullptr;
+    int n_as_ctiles = 0;
+    int2* as_work = nullptr;
+    int64_t n_as_work = 0;
+    uint32_t ops = 0;                 // rung-3 binary operators (bit o - OP_ADD)
+    int pe = 0;                       // partner pool size (compact 0..pe-1)
+    std::vector<void*> allocs;
+    ~R3Plan();
+};
+
+std::shared_ptr<R3Plan> build_r3_plan(const Space& sp, uint32_t r3_ops);
+
+// Per-call buffers of one problem's rung-3 screen.
+inline int r3_quads(int n) { return 4 * (int)((n + 15) / 16); }
+inline size_t r3_bmat_bytes(const R3Plan& p, int TP, int n) {
+    return (size_t)(p.n_ctiles + p.n_as_ctiles) * (TP + 2) * r3_quads(n) * 64 * 8;
+}
+inline size_t r3_pstat_bytes(const R3Plan& p, int TP) {
+    return (size_t)std::max(p.pe, 1) * (2 + TP + 2) * 8;
+}
+
+struct R3Launch {
+    const R3Plan* plan;
+    int n, ldn, TP, T, mode;
+    const double *Vf, *Rf, *Cf, *mu, *msq;
+    const uint8_t* valid;
+    const int64_t* mat_raw;
+    const double *Yn, *ysum;
+    const uint8_t* r2v;
+    const double *r2m, *r2q;
+    SpaceDev sd;
+    int64_t N;
+    double* scores;
+    unsigned long long* nscored;
+    int64_t* fix_ids;
+    unsigned long long* fix_cnt;
+    int64_t fix_cap;
+    double* bmat;                     // r3_bmat_bytes
+    double* pstat;                    // r3_pstat_bytes: max |x|, min |x| per partner,
+                                      // then the add/sub partner sums
+};
+
+void launch_r3(discover_ctx* ctx, const R3Launch& a, hipStream_t st);
+
+}  // namespace dsc

@@ -1,0 +1,655 @@
+// Operator-limited rung 3 on gfx950: screening of op3(f_i, g) for every
+// partner f_i of the pool and every rung-2 feature g, without storing g
+// (candidate generation by operators, Software Description; screening, the
+// SIS step of the cited SISSO method, Summary).
+//
+// mul / div / rdiv: the per-candidate sums are matrix products over samples.
+// A wave holds GT blocks of 16 rung-2 features (rows, regenerated in
+// registers from their two rung-1 operands, 4 consecutive samples per lane)
+// and one tile of 16 partner columns.  For every target t, the products
+// sum_s a_s (x_s y_ts) give P_t, sum_s a_s x_s gives S1 and sum_s a_s^2 x_s^2
+// gives S2, where a = g (mul, and rdiv with x replaced by 1/x) or a = 1/g
+// (div).  The right-hand operands [x y_t | x | x^2] of every column tile are
+// laid out once per call by k_r3_bmat, in the lane order of
+// v_mfma_f64_16x16x4f64 (B[k][j] from lane j + 16k, four samples per lane),
+// so a wave reads each as one 32-byte load per lane.
+//
+// The one-pass moments are unshifted: with kappa = S2 / (S2 - S1^2/n) the
+// rounding error of every score is below 2.5 n u kappa (u = 2^-53; n sums
+// of rounded products, plus the variance's cancellation), inside the
+// selection margin 4 n u KAPPA_MAX for kappa <= KAPPA_MAX.  Candidates with
+// a larger kappa, or whose values might overflow, are listed for the exact
+// two-pass fix-up; candidates whose values are certainly not finite (a
+// division by an exact zero) are left invalid.
+#include "dsc_r3.h"
+
+#include <algorithm>
+#include <map>
+#include <string>
+
+namespace dsc {
+
+namespace {
+
+constexpr double R3_KAPPA_MAX = 64.0;   // same bound as the other fast screens
+constexpr double R3_BIG = 1e150;        // |f| below this: f and n f^2 stay finite
+constexpr double R3_TINY = 1e-300;      // |g| above this: 1/g is finite
+constexpr double R3_TAU_CONST = 1e-8;
+constexpr double R3_TAU_CANCEL_FAST = 1e-12;
+
+typedef double r3_v4d __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int r3_wave() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
+// Slot of each active lane in a list (lane order), one atomic per wave.
+__device__ __forceinline__ unsigned long long r3_slot(unsigned long long* ctr) {
+    const uint64_t m = __builtin_amdgcn_ballot_w64(true);
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((long long)m) - 1;
+    unsigned long long base = 0;
+    if (lane == leader) base = atomicAdd(ctr, (unsigned long long)__popcll(m));
+    base = __shfl(base, leader, 64);
+    return base + (unsigned long long)__popcll(m & ((1ull << lane) - 1ull));
+}
+
+__device__ __forceinline__ double r3_un(int op, double a) {
+    switch (op) {
+    case OP_EXP: return exp(a);
+    case OP_LOG: return log(a);
+    case OP_SQRT: return sqrt(a);
+    default: return a * a;               // OP_SQ (OP_INV reads the reciprocal row)
+    }
+}
+
+// Rung-2 operator applied to operands already loaded: x from row p1, y from
+// row p2 of r3_rows (reciprocal rows where the operator divides).
+__device__ __forceinline__ r3_v4d r3_combine(int op2, r3_v4d x, r3_v4d y) {
+    switch (op2) {
+    case OP_EXP: return r3_v4d{exp(x.x), exp(x.y), exp(x.z), exp(x.w)};
+    case OP_LOG: return r3_v4d{log(x.x), log(x.y), log(x.z), log(x.w)};
+    case OP_SQRT: return r3_v4d{sqrt(x.x), sqrt(x.y), sqrt(x.z), sqrt(x.w)};
+    case OP_SQ: return x * x;
+    case OP_INV: return x;
+    case OP_ADD: return x + y;
+    case OP_SUB: return x - y;
+    default: return x * y;               // OP_MUL, OP_DIV, OP_RDIV
+    }
+}
+
+// Operand rows of rung-2 feature (k, l, op2): the combine above of rows p1
+// and p2 gives its values (the formulas of the rung-2 screen: a division
+// multiplies by the stored reciprocal).
+__device__ __forceinline__ void r3_rows(const double* Vf, const double* Rf, int64_t ldn, int k, int l,
+                                        int op2, const double*& p1, const double*& p2) {
+    const int64_t kk = k < 0 ? 0 : k;
+    if (op2 < OP_ADD) {
+        p1 = (op2 == OP_INV ? Rf : Vf) + (int64_t)l * ldn;
+        p2 = p1;
+    } else if (op2 == OP_RDIV) {
+        p1 = Vf + (int64_t)l * ldn;
+        p2 = Rf + kk * ldn;
+    } else {
+        p1 = Vf + kk * ldn;
+        p2 = (op2 == OP_DIV ? Rf : Vf) + (int64_t)l * ldn;
+    }
+}
+
+__device__ __forceinline__ double r3_regen1(const double* __restrict__ Vf, const double* __restrict__ Rf,
+                                            int64_t ldn, int k, int l, int op2, int s) {
+    const double b = Vf[(int64_t)l * ldn + s];
+    if (k < 0) return op2 == OP_INV ? Rf[(int64_t)l * ldn + s] : r3_un(op2, b);
+    const double a = Vf[(int64_t)k * ldn + s];
+    switch (op2) {
+    case OP_ADD: return a + b;
+    case OP_SUB: return a - b;
+    case OP_MUL: return a * b;
+    case OP_DIV: return a * Rf[(int64_t)l * ldn + s];
+    default: return b * Rf[(int64_t)k * ldn + s];
+    }
+}
+
+__device__ __forceinline__ double r3_rcp(double g) {
+    double r = __builtin_amdgcn_rcp(g);
+    r = fma(r, fma(-g, r, 1.0), r);
+    return fma(r, fma(-g, r, 1.0), r);
+}
+
+__device__ __forceinline__ void r3_rec(int2 rc, int& k, int& l, int& op2) {
+    k = rc.x;
+    l = rc.y & 0x0FFFFFFF;
+    op2 = (int)((unsigned)rc.y >> 28);
+}
+
+__device__ __forceinline__ int64_t r3_j2(const SpaceDev& sd, const int64_t* mat_raw, int k, int l, int op2) {
+    return k < 0 ? unary_id(sd, 2, op2, mat_raw[l]) : pair_id(sd, 2, op2, mat_raw[k], mat_raw[l]);
+}
+
+// ------------------------------------------------------------ set-up
+// max |x| and min |x| of every partner over the n samples.
+__global__ __launch_bounds__(256) void k_r3_pstat(int n, int64_t ldn, int pe, const double* __restrict__ Vf,
+                                                  double* __restrict__ pstat) {
+    const int p = blockIdx.x;
+    double mx = 0.0, mn = INFINITY;
+    for (int s = threadIdx.x; s < n; s += 256) {
+        const double v = fabs(Vf[(int64_t)p * ldn + s]);
+        mx = fmax(mx, v);
+        mn = fmin(mn, v);
+    }
+    __shared__ double smx[256], smn[256];
+    smx[threadIdx.x] = mx;
+    smn[threadIdx.x] = mn;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            smx[threadIdx.x] = fmax(smx[threadIdx.x], smx[threadIdx.x + o]);
+            smn[threadIdx.x] = fmin(smn[threadIdx.x], smn[threadIdx.x + o]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        pstat[p] = smx[0];
+        pstat[pe + p] = smn[0];
+    }
+}
+
+// Per-partner sums for add / sub: pc[p (TP + 2) + t] = sum_s x_s y_ts (t <
+// TP), sum x (t = TP), sum x^2 (t = TP + 1); one block per partner, a fixed
+// reduction order.
+__global__ __launch_bounds__(256) void k_r3_pconst(int n, int64_t ldn, int TP, const double* __restrict__ Vf,
+                                                   const double* __restrict__ Yn, double* __restrict__ pc) {
+    const int p = blockIdx.x;
+    __shared__ double part[256];
+    for (int t = 0; t < TP + 2; t++) {
+        double a = 0.0;
+        for (int s = threadIdx.x; s < n; s += 256) {
+            const double x = Vf[(int64_t)p * ldn + s];
+            a += t < TP ? x * Yn[(int64_t)t * ldn + s] : t == TP ? x : x * x;
+        }
+        part[threadIdx.x] = a;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if ((int)threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) pc[(int64_t)p * (TP + 2) + t] = part[0];
+        __syncthreads();
+    }
+}
+
+// Right-hand operands: bmat[((c TK + t) NQ + q) 64 + 4 j + e] = column j of
+// tile c, kind t, sample 4q + e; kinds t < TP: x y_t, t = TP: x, TP+1: x^2,
+// with x = f_p (mul, div and add/sub columns), 1/f_p (rdiv columns) or 1
+// (the column of ones of an add/sub tile); zero for padding columns and
+// samples >= n.
+__global__ __launch_bounds__(256) void k_r3_bmat(int n, int64_t ldn, int TP, int NQ, int nct,
+                                                 const int32_t* __restrict__ coldesc,
+                                                 const double* __restrict__ Vf, const double* __restrict__ Rf,
+                                                 const double* __restrict__ Yn, double* __restrict__ bmat) {
+    const int TK = TP + 2;
+    const int64_t total = (int64_t)nct * TK * NQ * 64;
+    for (int64_t f = (int64_t)blockIdx.x * 256 + threadIdx.x; f < total; f += (int64_t)gridDim.x * 256) {
+        const int e = (int)(f & 3), j = (int)((f >> 2) & 15);
+        const int64_t r = f >> 6;
+        const int q = (int)(r % NQ);
+        const int64_t ct_t = r / NQ;
+        const int t = (int)(ct_t % TK), c = (int)(ct_t / TK);
+        const int s = 4 * q + e;
+        const int32_t d = coldesc[c * 16 + j];
+        double v = 0.0;
+        if (d >= 0 && s < n) {
+            const int p = d & 0xFFFF, kind = d >> 16;
+            const double x = kind == 3 ? 1.0 : kind == 1 ? Rf[(int64_t)p * ldn + s] : Vf[(int64_t)p * ldn + s];
+            v = t < TP ? x * Yn[(int64_t)t * ldn + s] : t == TP ? x : x * x;
+        }
+        bmat[f] = v;
+    }
+}
+
+// ------------------------------------------------------------ MFMA screen
+struct R3mArgs {
+    const int2* grec;
+    int64_t n_grec;
+    const int2* work;         // add / sub: (row tile, column tile) per wave
+    int64_t n_work;
+    const double* pconst;     // add / sub: per-partner sums (k_r3_pconst)
+    const int32_t* coldesc;
+    int n_gct, n_gblk, NQ, n, T, mode;
+    int64_t ldn;
+    const double* bmat;
+    const double *Vf, *Rf;
+    const double* pstat;
+    int pe;
+    uint32_t ops;
+    const uint8_t* valid;
+    const int64_t* mat_raw;
+    const uint8_t* r2v;
+    const double* ysum;
+    SpaceDev sd;
+    int64_t N;
+    double* scores;
+    unsigned long long* nscored;
+    int64_t* fix_ids;
+    unsigned long long* fix_cnt;
+    int64_t fix_cap;
+};
+
+template <int TP, int GT, bool AS>
+__global__ __launch_bounds__(256) void k_r3_mm(R3mArgs g) {
+    constexpr int TK = TP + 2;
+    static_assert(!AS || GT == 1, "add/sub tiles come one per wave");
+    const int lane = threadIdx.x & 63;
+    const int r16 = lane & 15, kq = lane >> 4;
+    int ct;
+    int64_t tile0;
+    if (AS) {                                          // explicit (row tile, column tile) list
+        const int64_t w = (int64_t)blockIdx.x * 4 + r3_wave();
+        if (w >= g.n_work) return;
+        const int2 wk = g.work[w];
+        tile0 = wk.x;
+        ct = wk.y;
+    } else {
+        ct = blockIdx.x / g.n_gblk;                    // column tile (slowest: its operands stay in L2)
+        const int gb = blockIdx.x - ct * g.n_gblk;
+        tile0 = ((int64_t)gb * 4 + r3_wave()) * GT;
+        if (tile0 * 16 >= g.n_grec) return;
+    }
+    const bool hk = !AS && ct >= g.n_gct;              // rows hold 1/g (div columns)
+    const double* __restrict__ Vf = g.Vf;
+    const double* __restrict__ Rf = g.Rf;
+
+    // every tile's records share one operator (runs are padded to 16), so
+    // the regeneration's branches are uniform; absent rows read feature 0
+    int kk[GT], ll[GT], oo[GT];
+    bool rok[GT];
+    int64_t j2[GT];
+#pragma unroll
+    for (int u = 0; u < GT; u++) {
+        const int64_t t16 = min(tile0 + u, (g.n_grec >> 4) - 1) * 16;
+        const int64_t rec = (tile0 + u) * 16 + r16;
+        int k = -2, l = 0, op2;
+        r3_rec(g.grec[rec < g.n_grec ? rec : t16], k, l, op2);
+        oo[u] = __builtin_amdgcn_readfirstlane(op2);
+        rok[u] = rec < g.n_grec && k != -2;
+        j2[u] = rok[u] ? r3_j2(g.sd, g.mat_raw, k, l, op2) : 0;
+        rok[u] = rok[u] && g.r2v[j2[u] - g.sd.off[2]];
+        kk[u] = oo[u] < OP_ADD ? -1 : (rok[u] ? k : 0);
+        ll[u] = rok[u] ? l : 0;
+    }
+    const double* p1[GT];
+    const double* p2[GT];
+#pragma unroll
+    for (int u = 0; u < GT; u++) r3_rows(Vf, Rf, g.ldn, kk[u], ll[u], oo[u], p1[u], p2[u]);
+    r3_v4d acc[GT][TK];
+#pragma unroll
+    for (int u = 0; u < GT; u++)
+#pragma unroll
+        for (int t = 0; t < TK; t++) acc[u][t] = r3_v4d{0.0, 0.0, 0.0, 0.0};
+    double gmx[GT], gmn[GT];
+#pragma unroll
+    for (int u = 0; u < GT; u++) { gmx[u] = 0.0; gmn[u] = INFINITY; }
+
+    const double* bp = g.bmat + (int64_t)ct * TK * g.NQ * 64 + lane * 4;
+    const int nm = g.NQ >> 2;
+    for (int m = 0; m < nm; m++) {
+        const int s = 16 * m + 4 * kq;
+        r3_v4d A[GT], A2[GT];
+#pragma unroll
+        for (int u = 0; u < GT; u++) {
+            r3_v4d v = r3_combine(oo[u], *(const r3_v4d*)(p1[u] + s), *(const r3_v4d*)(p2[u] + s));
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const bool in = rok[u] && s + e < g.n;
+                const double x = in ? v[e] : 0.0;
+                v[e] = x;
+                if (in) {
+                    gmx[u] = fmax(gmx[u], fabs(x));
+                    gmn[u] = fmin(gmn[u], fabs(x));
+                }
+                if (hk) v[e] = in ? r3_rcp(x) : 0.0;
+            }
+            A[u] = v;
+            A2[u] = v * v;
+        }
+#pragma unroll
+        for (int t = 0; t < TK; t++) {
+            const r3_v4d b = *(const r3_v4d*)(bp + ((int64_t)t * g.NQ + 4 * m) * 64);
+#pragma unroll
+            for (int u = 0; u < GT; u++) {
+                const r3_v4d a = t == TK - 1 ? A2[u] : A[u];
+                acc[u][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, acc[u][t], 0, 0, 0);
+                acc[u][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.y, acc[u][t], 0, 0, 0);
+                acc[u][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.z, b.z, acc[u][t], 0, 0, 0);
+                acc[u][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.w, b.w, acc[u][t], 0, 0, 0);
+            }
+        }
+    }
+    // row ranges over the four sample groups of each row
+#pragma unroll
+    for (int u = 0; u < GT; u++) {
+        gmx[u] = fmax(gmx[u], __shfl_xor(gmx[u], 16, 64));
+        gmx[u] = fmax(gmx[u], __shfl_xor(gmx[u], 32, 64));
+        gmn[u] = fmin(gmn[u], __shfl_xor(gmn[u], 16, 64));
+        gmn[u] = fmin(gmn[u], __shfl_xor(gmn[u], 32, 64));
+    }
+    // this lane's column: D[i][j] sits in lane j + 16 (i mod 4), register i / 4
+    const double nn = (double)g.n;
+    unsigned cnt = 0;
+    if (AS) {
+        // column 15 holds the ones: sum g y_t, sum g, sum g^2 of each row; a
+        // partner column holds sum x g.  The add / sub moments follow from
+        // these and the partner's own sums:
+        //   S1 = Sx +- Sg, S2 = Sx2 +- 2 Sxg + Sg2, P_t = Sxy_t +- Sgy_t.
+        // Their rounding error is below 3.2 n u kappa' with kappa' =
+        // (Sx2 + Sg2) / (S2 - S1^2/n), so kappa' <= KAPPA_MAX keeps every
+        // score inside the selection margin; other pairs go to the fix-up.
+        const int32_t cd = g.coldesc[ct * 16 + r16];
+        const int p = cd & 0xFFFF;
+        const bool colok = cd >= 0 && (cd >> 16) == 0 && g.valid[p];
+        const int64_t praw = colok ? g.mat_raw[p] : 0;
+        const int src = (lane & 48) | 15;
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const int i = kq + 4 * r;
+            double gs[TK];
+#pragma unroll
+            for (int t = 0; t < TK; t++) gs[t] = __shfl(acc[0][t][r], src, 64);
+            const bool ok = __shfl((int)rok[0], i, 64) != 0 && colok;
+            const int64_t gj = __shfl(j2[0], i, 64);
+            if (!ok) continue;
+            const double* pc = g.pconst + (int64_t)p * TK;
+            const double Sxg = acc[0][TP][r];
+            const double A = pc[TP + 1] + gs[TP + 1];
+#pragma unroll
+            for (int o = 0; o < 2; o++) {
+                if (!((g.ops >> o) & 1u)) continue;
+                const double sg = o == 0 ? 1.0 : -1.0;
+                const int64_t id = pair_id(g.sd, 3, OP_ADD + o, praw, gj);
+                const double S1 = pc[TP] + sg * gs[TP];
+                const double S2 = pc[TP + 1] + 2.0 * sg * Sxg + gs[TP + 1];
+                const double varn = S2 - S1 * (S1 / nn);
+                const double kappa = varn > 0.0 ? A / varn : INFINITY;
+                if (!(S2 < INFINITY) || !(kappa <= R3_KAPPA_MAX) || S2 <= R3_TAU_CANCEL_FAST * A) {
+                    const unsigned long long slot = r3_slot(g.fix_cnt);
+                    if ((int64_t)slot < g.fix_cap) g.fix_ids[slot] = id;
+                    continue;
+                }
+                const double isd = 1.0 / sqrt(varn);
+                cnt++;
+                if (g.mode == DISCOVER_SCORE_MAX) {
+                    double best = 0.0;
+#pragma unroll
+                    for (int t = 0; t < TP; t++)
+                        if (t < g.T) best = fmax(best, fabs((pc[t] + sg * gs[t] - S1 * (g.ysum[t] / nn)) * isd));
+                    g.scores[id] = best;
+                } else {
+#pragma unroll
+                    for (int t = 0; t < TP; t++)
+                        if (t < g.T)
+                            g.scores[(int64_t)t * g.N + id] = fabs((pc[t] + sg * gs[t] - S1 * (g.ysum[t] / nn)) * isd);
+                }
+            }
+        }
+    } else {
+        const int32_t cd = g.coldesc[ct * 16 + r16];
+        const int p = cd & 0xFFFF, kind = cd >> 16;
+        const int op3 = kind == 0 ? OP_MUL : kind == 1 ? OP_RDIV : OP_DIV;
+        const bool colok = cd >= 0 && ((g.ops >> (op3 - OP_ADD)) & 1u) && g.valid[p];
+        const double xmx = colok ? g.pstat[p] : 0.0, xmn = colok ? g.pstat[g.pe + p] : 1.0;
+        const int64_t praw = colok ? g.mat_raw[p] : 0;
+    #pragma unroll
+        for (int u = 0; u < GT; u++) {
+    #pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int i = kq + 4 * r;                      // row of this register
+                const bool ok = __shfl((int)rok[u], i, 64) != 0 && colok;
+                const int64_t gj = __shfl(j2[u], i, 64);
+                const double rmx = __shfl(gmx[u], i, 64), rmn = __shfl(gmn[u], i, 64);
+                if (!ok) continue;
+                const int64_t id = pair_id(g.sd, 3, op3, praw, gj);
+                // finiteness of the candidate's values
+                bool sure = true;
+                if (op3 == OP_MUL) {
+                    sure = rmx * xmx < R3_BIG;
+                } else if (op3 == OP_DIV) {
+                    if (rmn == 0.0) continue;                  // x / 0: not finite
+                    sure = rmn >= R3_TINY && xmx < R3_BIG * rmn;
+                } else {
+                    if (xmn == 0.0) continue;                  // g / 0: not finite
+                    sure = xmn >= R3_TINY && rmx < R3_BIG * xmn;
+                }
+                const double S1 = acc[u][TP][r], S2 = acc[u][TP + 1][r];
+                const double varn = S2 - S1 * (S1 / nn);
+                const double kappa = varn > 0.0 ? S2 / varn : INFINITY;
+                if (!sure || !(kappa <= R3_KAPPA_MAX)) {
+                    const unsigned long long slot = r3_slot(g.fix_cnt);
+                    if ((int64_t)slot < g.fix_cap) g.fix_ids[slot] = id;
+                    continue;
+                }
+                const double isd = 1.0 / sqrt(varn);
+                cnt++;
+                if (g.mode == DISCOVER_SCORE_MAX) {
+                    double best = 0.0;
+    #pragma unroll
+                    for (int t = 0; t < TP; t++)
+                        if (t < g.T) best = fmax(best, fabs((acc[u][t][r] - S1 * (g.ysum[t] / nn)) * isd));
+                    g.scores[id] = best;
+                } else {
+    #pragma unroll
+                    for (int t = 0; t < TP; t++)
+                        if (t < g.T)
+                            g.scores[(int64_t)t * g.N + id] = fabs((acc[u][t][r] - S1 * (g.ysum[t] / nn)) * isd);
+                }
+            }
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor((int)cnt, o, 64);
+    if (lane == 0 && cnt) atomicAdd(g.nscored, (unsigned long long)cnt);
+}
+
+template <class T>
+T* r3_up(R3Plan& P, const std::vector<T>& v) {
+    void* p = nullptr;
+    const size_t bytes = std::max<size_t>(v.size() * sizeof(T), 16);
+    if (hipMalloc(&p, bytes) != hipSuccess) DSC_FAIL(DISCOVER_E_NOMEM, "rung-3 plan allocation failed");
+    P.allocs.push_back(p);
+    if (!v.empty()) DSC_HIP(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return (T*)p;
+}
+
+template <int TP, int GT>
+void launch_mm(R3mArgs a, int nct, hipStream_t st) {
+    const int64_t ntl = (a.n_grec + 15) / 16;
+    a.n_gblk = (int)((ntl + 4 * GT - 1) / (4 * GT));
+    const int64_t blocks = (int64_t)a.n_gblk * nct;
+    DSC_REQUIRE(blocks < ((int64_t)1 << 31), "rung-3 grid too large");
+    k_r3_mm<TP, GT, false><<<(unsigned)blocks, 256, 0, st>>>(a);
+}
+
+template <int TP>
+void launch_as(const R3mArgs& a, hipStream_t st) {
+    const int64_t blocks = (a.n_work + 3) / 4;
+    DSC_REQUIRE(blocks < ((int64_t)1 << 31), "rung-3 add/sub grid too large");
+    k_r3_mm<TP, 1, true><<<(unsigned)blocks, 256, 0, st>>>(a);
+}
+
+}  // namespace
+
+std::shared_ptr<R3Plan> build_r3_plan(const Space& sp, uint32_t r3_ops) {
+    auto P = std::make_shared<R3Plan>();
+    const SpaceDev& d = sp.d;
+    const int B = sp.B, Bq = B > 0 ? B : 1;
+    P->ops = r3_ops;
+    P->pe = sp.rung_start[d.pool[3] + 1];
+    DSC_REQUIRE(P->pe < 65536, "rung-3 partner pool too large");
+    const int32_t c0 = sp.rung_start[1], c1 = sp.rung_start[2];
+    DSC_REQUIRE(c1 < (1 << 28), "rung-1 operand count too large");
+    const int pool2 = d.pool[2];
+    const bool addsub = (r3_ops & 3u) != 0;
+    // every unit-legal rung-2 feature, in ID order, with its unit vector
+    std::vector<int2> rec;
+    std::vector<int32_t> gunit;
+    std::vector<int32_t> u2(Bq, 0);
+    auto push = [&](int k, int l, int o) {
+        rec.push_back(make_int2(k, l | (o << 28)));
+        if (addsub) gunit.insert(gunit.end(), u2.begin(), u2.end());
+    };
+    // each operator's run is padded to a multiple of 16 records (k = -2:
+    // no feature), so that the rows of a 16-row tile share one operator
+    auto pad16 = [&](int o) {
+        while (rec.size() % 16) {
+            rec.push_back(make_int2(-2, o << 28));
+            if (addsub) gunit.insert(gunit.end(), Bq, INT32_MIN);
+        }
+    };
+    for (int o = 0; o < OP_ADD; o++) {
+        if (d.block[2][o] < 0) continue;
+        for (int32_t l = c0; l < c1; l++)
+            if (unit_rule(o, B, &sp.mat_unit[(size_t)l * Bq], nullptr, u2.data())) push(-1, l, o);
+        pad16(o);
+    }
+    for (int o = OP_ADD; o <= OP_RDIV; o++) {
+        if (d.block[2][o] < 0) continue;
+        for (int32_t l = c0; l < c1; l++) {
+            const int32_t kmax = pool2 == 1 ? l : sp.rung_start[pool2 + 1];
+            for (int32_t k = 0; k < kmax; k++)
+                if (unit_rule(o, B, &sp.mat_unit[(size_t)k * Bq], &sp.mat_unit[(size_t)l * Bq], u2.data()))
+                    push(k, l, o);
+        }
+        pad16(o);
+    }
+    P->n_grec = (int64_t)rec.size();
+    // partner column tiles: per group of 8 partners, 8 mul then 8 rdiv
+    // columns (both against g); then the div columns (against 1/g)
+    const bool mul = (r3_ops >> (OP_MUL - OP_ADD)) & 1u, div = (r3_ops >> (OP_DIV - OP_ADD)) & 1u,
+               rdiv = (r3_ops >> (OP_RDIV - OP_ADD)) & 1u;
+    std::vector<int32_t> cols;
+    for (int g8 = 0; g8 < (P->pe + 7) / 8; g8++)
+        for (int kind = 0; kind < 2; kind++) {
+            if (kind == 0 ? !mul : !rdiv) continue;
+            for (int q = 0; q < 8; q++) {
+                const int p = 8 * g8 + q;
+                cols.push_back(p < P->pe ? (p | (kind << 16)) : -1);
+            }
+        }
+    while (cols.size() % 16) cols.push_back(-1);
+    P->n_gct = (int)(cols.size() / 16);
+    if (div) {
+        for (int p = 0; p < P->pe; p++) cols.push_back(p | (2 << 16));
+        while (cols.size() % 16) cols.push_back(-1);
+    }
+    P->n_ctiles = (int)(cols.size() / 16);
+    P->h_coldesc = cols;
+    if (P->n_grec && P->n_ctiles) {
+        P->grec = r3_up(*P, rec);
+        P->coldesc = r3_up(*P, cols);
+    }
+    // add / sub: records grouped by unit vector and operator, against
+    // column tiles of the partners with the same unit vector (15 at most)
+    // and a column of ones
+    if (addsub && P->n_grec) {
+        auto key = [&](const int32_t* u) { return std::string((const char*)u, sizeof(int32_t) * Bq); };
+        std::map<std::string, std::vector<int32_t>> pg;
+        for (int p = 0; p < P->pe; p++) pg[key(&sp.mat_unit[(size_t)p * Bq])].push_back(p);
+        std::map<std::string, std::map<int, std::vector<int64_t>>> byk;
+        for (int64_t r = 0; r < P->n_grec; r++) {
+            if (rec[r].x == -2) continue;
+            const std::string kk = B > 0 ? key(&gunit[(size_t)r * Bq]) : key(u2.data());
+            if (pg.count(kk)) byk[kk][(int)((unsigned)rec[r].y >> 28)].push_back(r);
+        }
+        std::vector<int2> arec, work;
+        std::vector<int32_t> acols;
+        for (auto& e : byk) {
+            const std::vector<int32_t>& pl = pg[e.first];
+            const int ct0 = (int)(acols.size() / 16);
+            for (size_t q = 0; q < pl.size(); q += 15) {
+                for (size_t z = 0; z < 15; z++) acols.push_back(q + z < pl.size() ? pl[q + z] : -1);
+                acols.push_back(3 << 16);                        // the ones
+            }
+            const int ct1 = (int)(acols.size() / 16);
+            for (auto& ro : e.second) {
+                const int64_t rt0 = (int64_t)arec.size() / 16;
+                for (int64_t r : ro.second) arec.push_back(rec[r]);
+                while (arec.size() % 16) arec.push_back(make_int2(-2, ro.first << 28));
+                const int64_t rt1 = (int64_t)arec.size() / 16;
+                for (int64_t rt = rt0; rt < rt1; rt++)
+                    for (int c = ct0; c < ct1; c++) work.push_back(make_int2((int)rt, c));
+            }
+        }
+        DSC_REQUIRE(arec.size() < ((size_t)1 << 35), "rung-3 add/sub list too large");
+        P->n_as_grec = (int64_t)arec.size();
+        P->n_as_ctiles = (int)(acols.size() / 16);
+        P->n_as_work = (int64_t)work.size();
+        if (P->n_as_work) {
+            P->as_grec = r3_up(*P, arec);
+            P->as_coldesc = r3_up(*P, acols);
+            P->as_work = r3_up(*P, work);
+        }
+    }
+    return P;
+}
+
+void launch_r3(discover_ctx* ctx, const R3Launch& a, hipStream_t st) {
+    const R3Plan& P = *a.plan;
+    const int NQ = r3_quads(a.n);
+    if (P.n_grec && P.n_ctiles) {
+        k_r3_pstat<<<(unsigned)P.pe, 256, 0, st>>>(a.n, a.ldn, P.pe, a.Vf, a.pstat);
+        check_launch("k_r3_pstat");
+        const int64_t tot = (int64_t)P.n_ctiles * (a.TP + 2) * NQ * 64;
+        k_r3_bmat<<<(unsigned)std::min<int64_t>(cdiv(tot, 256), 16384), 256, 0, st>>>(
+            a.n, a.ldn, a.TP, NQ, P.n_ctiles, P.coldesc, a.Vf, a.Rf, a.Yn, a.bmat);
+        check_launch("k_r3_bmat");
+        R3mArgs m{};
+        m.grec = P.grec; m.n_grec = P.n_grec; m.coldesc = P.coldesc; m.n_gct = P.n_gct;
+        m.NQ = NQ; m.n = a.n; m.T = a.T; m.mode = a.mode; m.ldn = a.ldn; m.bmat = a.bmat;
+        m.Vf = a.Vf; m.Rf = a.Rf; m.pstat = a.pstat; m.pe = P.pe; m.ops = P.ops;
+        m.valid = a.valid; m.mat_raw = a.mat_raw; m.r2v = a.r2v; m.ysum = a.ysum; m.sd = a.sd;
+        m.N = a.N; m.scores = a.scores; m.nscored = a.nscored; m.fix_ids = a.fix_ids;
+        m.fix_cnt = a.fix_cnt; m.fix_cap = a.fix_cap;
+        KTimer kt(ctx, st, "screen_r3");
+        switch (a.TP) {
+        // row tiles per wave: as many as keep two or three waves per SIMD
+        // with the accumulators in VGPRs (measured on gfx950: one tile per
+        // wave at 8 targets beats two tiles at one wave per SIMD)
+        case 1: launch_mm<1, 2>(m, P.n_ctiles, st); break;
+        case 2: launch_mm<2, 2>(m, P.n_ctiles, st); break;
+        case 4: launch_mm<4, 1>(m, P.n_ctiles, st); break;
+        case 8: launch_mm<8, 1>(m, P.n_ctiles, st); break;
+        default: launch_mm<16, 1>(m, P.n_ctiles, st); break;
+        }
+        check_launch("k_r3_mm");
+    }
+    if (P.n_as_work) {
+        double* bm = a.bmat + (size_t)P.n_ctiles * (a.TP + 2) * NQ * 64;
+        double* pc = a.pstat + 2 * P.pe;
+        k_r3_pconst<<<(unsigned)P.pe, 256, 0, st>>>(a.n, a.ldn, a.TP, a.Vf, a.Yn, pc);
+        check_launch("k_r3_pconst");
+        const int64_t tot = (int64_t)P.n_as_ctiles * (a.TP + 2) * NQ * 64;
+        k_r3_bmat<<<(unsigned)std::min<int64_t>(cdiv(tot, 256), 16384), 256, 0, st>>>(
+            a.n, a.ldn, a.TP, NQ, P.n_as_ctiles, P.as_coldesc, a.Vf, a.Rf, a.Yn, bm);
+        check_launch("k_r3_bmat");
+        R3mArgs m{};
+        m.grec = P.as_grec; m.n_grec = P.n_as_grec; m.work = P.as_work; m.n_work = P.n_as_work;
+        m.pconst = pc; m.coldesc = P.as_coldesc; m.n_gct = 0;
+        m.NQ = NQ; m.n = a.n; m.T = a.T; m.mode = a.mode; m.ldn = a.ldn; m.bmat = bm;
+        m.Vf = a.Vf; m.Rf = a.Rf; m.pstat = a.pstat; m.pe = P.pe; m.ops = P.ops;
+        m.valid = a.valid; m.mat_raw = a.mat_raw; m.r2v = a.r2v; m.ysum = a.ysum; m.sd = a.sd;
+        m.N = a.N; m.scores = a.scores; m.nscored = a.nscored; m.fix_ids = a.fix_ids;
+        m.fix_cnt = a.fix_cnt; m.fix_cap = a.fix_cap;
+        KTimer kt(ctx, st, "screen_r3_addsub");
+        switch (a.TP) {
+        case 1: launch_as<1>(m, st); break;
+        case 2: launch_as<2>(m, st); break;
+        case 4: launch_as<4>(m, st); break;
+        case 8: launch_as<8>(m, st); break;
+        default: launch_as<16>(m, st); break;
+        }
+        check_launch("k_r3_mm(add/sub)");
+    }
+}
+
+R3Plan::~R3Plan() {
+    for (void* p : allocs)
+        if (hipFree(p) != hipSuccess) { /* nothing to do */ }
+}
+
+}  // namespace dsc

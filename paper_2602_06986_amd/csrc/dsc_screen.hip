@@ -23,6 +23,7 @@
 #include "dsc_internal.h"
 #include "dsc_select.h"
 #include "dsc_space.h"
+#include "dsc_r3.h"
 
 #include <memory>
 #include <type_traits>
@@ -726,287 +727,6 @@ __global__ __launch_bounds__(64 * pair_split<LIST>()) void k_screen_pairs(ctab<P
 #undef S1
 #undef S2
 #undef DT
-}
-
-// ---------------------------------------------- operator-limited rung 3
-// Candidates op3(f_i, f_j2): i in the materialised partner pool (uniform
-// across the wave), j2 a rung-2 feature regenerated on the fly in every lane
-// from two rung-1 operands (never stored).  The wave's 64 rung-2 features
-// come from one rung-2 tile: (op2, l, 64 consecutive k) for binary op2,
-// (op2, 64 consecutive l) for unary op2, or a same-unit partner list.
-// Shifts: add/sub use centered operands, mul mu_i mu_j2, div mu_i / mu_j2,
-// rdiv mu_j2 / mu_i-type estimates (mu_j2 from the rung-2 screening pass).
-struct R3Args {
-    const int4* tiles;        // (op2, l or l0, k0 or list offset, -1 dense | count | -2 unary)
-    const int32_t* klist;
-    int64_t n_tiles;
-    int n, ldm, ldn, Mc, c1_lo, c1_hi, pe, B;
-    const double *Vs, *Rs, *Cs, *Vf, *Rf, *Cf, *mu, *mur;
-    const uint8_t* valid;
-    const int64_t* mat_raw;
-    const int32_t* mat_unit;
-    const uint8_t* r2v;
-    const double* r2m;
-    const double* r2q;
-    const double* msq;
-    const double* Yn;
-    const double* ysum;
-    int T, mode;
-    uint32_t opmask;          // rung-3 binary operators (bits 0..4 = add..rdiv)
-    SpaceDev sd;
-    int64_t N;
-    double* scores;
-    unsigned long long* nscored;
-    int64_t* fix_ids;
-    unsigned long long* fix_cnt;
-    int64_t fix_cap;
-};
-
-__device__ __forceinline__ bool dev_unit_rule(int op, int B, const int32_t* ua, const int32_t* ub,
-                                              int32_t* out) {
-    switch (op) {
-    case OP_EXP: case OP_LOG:
-        for (int k = 0; k < B; k++) if (ua[k]) return false;
-        for (int k = 0; k < B; k++) out[k] = 0;
-        return true;
-    case OP_SQRT:
-        for (int k = 0; k < B; k++) if (ua[k] & 1) return false;
-        for (int k = 0; k < B; k++) out[k] = ua[k] / 2;
-        return true;
-    case OP_SQ: for (int k = 0; k < B; k++) out[k] = 2 * ua[k]; return true;
-    case OP_INV: for (int k = 0; k < B; k++) out[k] = -ua[k]; return true;
-    case OP_ADD: case OP_SUB:
-        for (int k = 0; k < B; k++) if (ua[k] != ub[k]) return false;
-        for (int k = 0; k < B; k++) out[k] = ua[k];
-        return true;
-    case OP_MUL: for (int k = 0; k < B; k++) out[k] = ua[k] + ub[k]; return true;
-    case OP_DIV: for (int k = 0; k < B; k++) out[k] = ua[k] - ub[k]; return true;
-    default: for (int k = 0; k < B; k++) out[k] = ub[k] - ua[k]; return true;
-    }
-}
-
-constexpr int R3_SB = 2;              // samples regenerated ahead of their accumulation
-
-// Read-only operand arrays of the rung-3 kernel, read through the constant
-// address space: the kernel never writes them, so wave-uniform loads (the
-// primary operand, the targets, a binary tile's common operand) become
-// scalar loads even though the kernel stores scores between its loops.
-typedef const __attribute__((address_space(4))) double r3c_double;
-
-template <int OPS, int IC, int TP>
-__global__ __launch_bounds__(256) void k_screen_r3(R3Args g) {
-    constexpr int NOP = ((OPS >> 0) & 1) + ((OPS >> 1) & 1) + ((OPS >> 2) & 1) +
-                        ((OPS >> 3) & 1) + ((OPS >> 4) & 1);
-    const int64_t w = (int64_t)blockIdx.x * 4 + wave_id();
-    if (w >= g.n_tiles) return;
-    const int lane = threadIdx.x & 63;
-    const int4 tile = g.tiles[w];
-    const int op2 = tile.x;
-    // this lane's rung-2 feature: operands (k, l) compact, raw id j2
-    int k = -1, l = -1;
-    bool lok;
-    if (tile.w == -2) {                                   // unary op2 over 64 consecutive l
-        l = tile.y + lane;
-        lok = l < g.c1_hi;
-    } else if (tile.w == -1) {                            // binary op2, k = k0 + lane < l
-        l = tile.y;
-        k = tile.z + lane;
-        lok = k < l;
-    } else {                                              // binary op2, explicit partner list
-        l = tile.y;
-        lok = lane < tile.w;
-        k = g.klist[tile.z + (lok ? lane : 0)];
-    }
-    const int lc = lok ? l : g.c1_lo;
-    const int kc = (k >= 0 && lok) ? k : 0;
-    int64_t j2 = 0;
-    if (lok) j2 = tile.w == -2 ? unary_id(g.sd, 2, op2, g.mat_raw[lc])
-                              : pair_id(g.sd, 2, op2, g.mat_raw[kc], g.mat_raw[lc]);
-    const int64_t o2 = j2 - g.sd.off[2];
-    const bool ok2 = lok && g.r2v[o2];
-    const double mu2 = ok2 ? g.r2m[o2] : 1.0;
-    const double q2 = ok2 ? g.r2q[o2] : 1.0;
-    int32_t u2[DISCOVER_MAX_UNITS];
-    if (g.B > 0) {
-        bool leg = dev_unit_rule(op2, g.B, g.mat_unit + (int64_t)(tile.w == -2 ? lc : kc) * g.B,
-                                 g.mat_unit + (int64_t)lc * g.B, u2);
-        (void)leg;                                        // ok2 already implies legality
-    }
-    const bool want_rcp = (OPS & 8) != 0;
-    const int nn_i = g.n;
-    const double nn = (double)g.n;
-    unsigned cnt = 0;
-    for (int i0 = 0; i0 < g.pe; i0 += IC) {
-        // per-lane legality of add/sub partners (unit exponents must agree)
-        bool addok[IC];
-        bool any_add = false;
-#pragma unroll
-        for (int ii = 0; ii < IC; ii++) {
-            const int i = min(i0 + ii, g.pe - 1);
-            bool eq = true;
-            for (int b = 0; b < g.B; b++) eq = eq && (g.mat_unit[(int64_t)i * g.B + b] == u2[b]);
-            addok[ii] = ok2 && (i0 + ii < g.pe) && eq;
-            any_add |= addok[ii];
-        }
-        const bool wave_add = (OPS & 3) && __any(any_add);
-        double sh[IC][NOP];
-#pragma unroll
-        for (int ii = 0; ii < IC; ii++) {
-            const int i = min(i0 + ii, g.pe - 1);
-            const double mi = g.mu[i], mri = g.mur[i];
-            int q = 0;
-            if (OPS & 1) sh[ii][q++] = 0.0;
-            if (OPS & 2) sh[ii][q++] = 0.0;
-            if (OPS & 4) sh[ii][q++] = mi * mu2;
-            if (OPS & 8) sh[ii][q++] = mu2 != 0.0 ? mi / mu2 : 0.0;
-            if (OPS & 16) sh[ii][q++] = mu2 * mri;
-        }
-        double acc[IC][NOP][2 + TP];
-#pragma unroll
-        for (int ii = 0; ii < IC; ii++)
-#pragma unroll
-            for (int q = 0; q < NOP; q++)
-#pragma unroll
-                for (int v = 0; v < 2 + TP; v++) acc[ii][q][v] = 0.0;
-        r3c_double* __restrict__ Vs = (r3c_double*)g.Vs;
-        r3c_double* __restrict__ Rs = (r3c_double*)g.Rs;
-        r3c_double* __restrict__ Vf = (r3c_double*)g.Vf;
-        r3c_double* __restrict__ Rf = (r3c_double*)g.Rf;
-        r3c_double* __restrict__ Cf = (r3c_double*)g.Cf;
-        r3c_double* __restrict__ Yn = (r3c_double*)g.Yn;
-        // regenerated rung-2 value of sample s (uniform branches on the tile)
-        auto regen = [&](int s, double& f2, double& rf2) {
-            if (tile.w == -2) {
-                const int64_t so = (int64_t)s * g.ldm + lc;
-                const double a = Vs[so];
-                f2 = op2 == OP_INV ? Rs[so] : op2 == OP_SQ ? a * a : apply_op(op2, a, 0.0);
-            } else {
-                // binary op2: the second operand l is the same for the whole wave
-                const double a = Vs[(int64_t)s * g.ldm + kc];
-                const double b = Vf[(int64_t)tile.y * g.ldn + s];
-                switch (op2) {
-                case OP_ADD: f2 = a + b; break;
-                case OP_SUB: f2 = a - b; break;
-                case OP_MUL: f2 = a * b; break;
-                case OP_DIV: f2 = a * Rf[(int64_t)tile.y * g.ldn + s]; break;
-                default: f2 = b * Rs[(int64_t)s * g.ldm + kc]; break;
-                }
-            }
-            rf2 = 0.0;
-            if (want_rcp) {
-                double r = __builtin_amdgcn_rcp(f2);
-                r = fma(r, fma(-f2, r, 1.0), r);
-                rf2 = fma(r, fma(-f2, r, 1.0), r);
-            }
-        };
-        // moments of sample s (straight-line)
-        auto accum = [&](int s, double f2, double rf2) {
-            const double f2c = f2 - mu2;
-            double y[TP];
-#pragma unroll
-            for (int t = 0; t < TP; t++) y[t] = Yn[(int64_t)t * g.ldn + s];
-#pragma unroll
-            for (int ii = 0; ii < IC; ii++) {
-                const int i = min(i0 + ii, g.pe - 1);
-                const double x = Vf[(int64_t)i * g.ldn + s];
-                const double xc = (OPS & 3) ? Cf[(int64_t)i * g.ldn + s] : 0.0;
-                const double rx = (OPS & 16) ? Rf[(int64_t)i * g.ldn + s] : 0.0;
-                double f[NOP];
-                int q = 0;
-                if (OPS & 1) { f[q] = xc + f2c; q++; }
-                if (OPS & 2) { f[q] = xc - f2c; q++; }
-                if (OPS & 4) { f[q] = fma(x, f2, -sh[ii][q]); q++; }
-                if (OPS & 8) { f[q] = fma(x, rf2, -sh[ii][q]); q++; }
-                if (OPS & 16) { f[q] = fma(f2, rx, -sh[ii][q]); q++; }
-#pragma unroll
-                for (int qq = 0; qq < NOP; qq++) {
-                    if (qq < ((OPS & 1) + ((OPS >> 1) & 1)) && !wave_add) continue;   // uniform
-                    acc[ii][qq][0] += f[qq];
-                    acc[ii][qq][1] = fma(f[qq], f[qq], acc[ii][qq][1]);
-#pragma unroll
-                    for (int t = 0; t < TP; t++) acc[ii][qq][2 + t] = fma(f[qq], y[t], acc[ii][qq][2 + t]);
-                }
-            }
-        };
-        // samples in groups of R3_SB: the branchy regeneration first, then the
-        // straight-line accumulation (same order of every sum as one at a time)
-        int s = 0;
-        for (; s + R3_SB <= nn_i; s += R3_SB) {
-            double f2v[R3_SB], rf2v[R3_SB];
-#pragma unroll
-            for (int u = 0; u < R3_SB; u++) regen(s + u, f2v[u], rf2v[u]);
-#pragma unroll
-            for (int u = 0; u < R3_SB; u++) accum(s + u, f2v[u], rf2v[u]);
-        }
-        for (; s < nn_i; s++) {
-            double f2, rf2;
-            regen(s, f2, rf2);
-            accum(s, f2, rf2);
-        }
-        // finalise the IC x NOP candidates of this chunk
-#pragma unroll
-        for (int ii = 0; ii < IC; ii++) {
-            const int i = i0 + ii;
-            if (i >= g.pe) continue;
-            int q = 0;
-#pragma unroll
-            for (int o = 0; o < 5; o++) {
-                if (!((OPS >> o) & 1)) continue;
-                const int qq = q++;
-                // score slots start as NaN: unit-illegal or invalid candidates are
-                // simply not written
-                if (!((g.opmask >> o) & 1) || !ok2 || !g.valid[i]) continue;
-                if (o < 2 && !addok[ii]) continue;
-                const int64_t id = pair_id(g.sd, 3, OP_ADD + o, g.mat_raw[i], j2);
-                const double nanv = __longlong_as_double(-1LL);
-                const double S1v = acc[ii][qq][0], S2v = acc[ii][qq][1];
-                const double m1 = S1v / nn, varn = S2v - S1v * m1;
-                if (!(S2v < INFINITY) || !(fabs(S1v) < INFINITY)) continue;
-                double kappa = varn > 0.0 ? S2v / varn : INFINITY;
-                if (o < 2) {                                      // possible cancellation
-                    const double c0 = o == 0 ? g.mu[i] + mu2 : g.mu[i] - mu2;
-                    const double ff = S2v + 2.0 * c0 * S1v + nn * c0 * c0;
-                    if (ff <= 1e-12 * nn * (g.msq[i] + q2)) kappa = INFINITY;
-                }
-                if (!(kappa <= KAPPA_MAX)) {
-                    const unsigned long long slot = wave_slot(g.fix_cnt);
-                    if ((int64_t)slot < g.fix_cap) {
-                        g.fix_ids[slot] = id;
-                        for (int t = 0; t < (g.mode ? 1 : g.T); t++) g.scores[(int64_t)t * g.N + id] = nanv;
-                        continue;
-                    }
-                }
-                double shift = sh[ii][qq];
-                if (o == 0) shift = g.mu[i] + mu2;
-                if (o == 1) shift = g.mu[i] - mu2;
-                const double mean = shift + m1;
-                const bool nonconst = varn / nn > TAU_CONST * TAU_CONST * (varn / nn + mean * mean);
-                if (kappa <= KAPPA_MAX && !nonconst) {
-                    for (int t = 0; t < (g.mode ? 1 : g.T); t++) g.scores[(int64_t)t * g.N + id] = nanv;
-                    continue;
-                }
-                const double isd = 1.0 / sqrt(varn);
-                double out[TP], best = 0.0;
-#pragma unroll
-                for (int t = 0; t < TP; t++) {
-                    out[t] = fabs((acc[ii][qq][2 + t] - S1v * g.ysum[t] / nn) * isd);
-                    if (t < g.T) best = fmax(best, out[t]);
-                }
-                const double err = 4.0 * nn * EPS64 * kappa;
-                const bool precise = kappa <= KAPPA_MAX;
-                cnt++;
-                if (g.mode == DISCOVER_SCORE_MAX) {
-                    g.scores[id] = precise ? best : -(best + err);
-                } else {
-#pragma unroll
-                    for (int t = 0; t < TP; t++)
-                        if (t < g.T) g.scores[(int64_t)t * g.N + id] = precise ? out[t] : -(out[t] + err);
-                }
-            }
-        }
-    }
-    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor((int)cnt, o, 64);
-    if (lane == 0 && cnt) atomicAdd(g.nscored, (unsigned long long)cnt);
 }
 
 // -------------------------------------------- reduced-precision screen
@@ -2516,9 +2236,7 @@ struct Plan {
     std::vector<int4> ltiles;                 // list mode: (jc, list offset, count)
     int32_t* ilist = nullptr;
     uint32_t list_ops = 0;
-    int4* r3tiles = nullptr;                  // rung-3 tiles over rung-2 operands
-    int64_t n_r3tiles = 0;
-    int32_t* mat_unit = nullptr;
+    std::shared_ptr<R3Plan> r3;               // operator-limited rung 3 work lists
     uint32_t r3_ops = 0;
     std::string key;
 
@@ -2643,30 +2361,9 @@ static std::shared_ptr<Plan> get_plan(discover_ctx* ctx, const discover_problem&
     }
     P->ilist = P->up(il);
     if (sp.stream3) {
-        // rung-3 candidates op3(i, j2): one wave per 64 rung-2 features j2
-        std::vector<int4> t3;
-        const int32_t c0 = sp.rung_start[1], c1 = sp.rung_start[2];
-        for (int o = 0; o < OP_ADD; o++) {
-            if (sd.block[2][o] < 0) continue;
-            for (int32_t l0 = c0; l0 < c1; l0 += 64) t3.push_back(make_int4(o, l0, 0, -2));
-        }
-        for (int o = OP_ADD; o <= OP_RDIV; o++) {
-            if (sd.block[2][o] < 0) continue;
-            const bool addcls = o <= OP_SUB;
-            if (units && addcls) {
-                for (const int4& q : P->ltiles) t3.push_back(make_int4(o, q.x, q.y, q.z));
-            } else {
-                for (int32_t l = c0; l < c1; l++)
-                    for (int32_t k0 = 0; k0 < l; k0 += 64) t3.push_back(make_int4(o, l, k0, -1));
-            }
-        }
-        P->r3tiles = P->up(t3);
-        P->n_r3tiles = (int64_t)t3.size();
-        std::vector<int32_t> mu(sp.mat_unit.begin(), sp.mat_unit.end());
-        if (mu.empty()) mu.push_back(0);
-        P->mat_unit = P->up(mu);
         for (int o = OP_ADD; o <= OP_RDIV; o++)
             if (sd.block[3][o] >= 0) P->r3_ops |= 1u << (o - OP_ADD);
+        P->r3 = build_r3_plan(sp, P->r3_ops);
     }
     ctx->plans[key] = P;
     return P;
@@ -2684,6 +2381,8 @@ struct Problem {
     double* r2m = nullptr;
     double* r2q = nullptr;
     void* ylp = nullptr;
+    double* r3b = nullptr;                    // rung-3 right-hand operands
+    double* r3p = nullptr;                    // rung-3 partner ranges
     int ldl = 0;
     int tile_j = 0;                           // dense pair kernel width used (0: not run)
     bool pairs = false;                       // streamed rung with pair operators
@@ -2709,9 +2408,10 @@ struct ListState {
 };
 
 // Pool entries whose values the rescoring keeps for the duplicate pairs:
-// up to 16 MB of values per list.
+// up to 1 GB of values per list (every entry of a pool of n = 2000 samples
+// up to 65,536 entries).
 static int64_t pool_vals_cap(int64_t cap, int n) {
-    return std::min<int64_t>(cap, ((int64_t)16 << 20) / (8 * (int64_t)std::max(n, 1)));
+    return std::min<int64_t>(cap, ((int64_t)1 << 30) / (8 * (int64_t)std::max(n, 1)));
 }
 
 // Allocate every problem's working memory for one call.
@@ -2756,6 +2456,9 @@ static void layout_problems(discover_ctx* ctx, const discover_problem* probs, in
         v.push_back(ar.add(L2 * 8));                                           // r2q
         P.ldl = (int)cdiv(P.n, 32) * 32;
         v.push_back(ar.add(prm.precision != DISCOVER_FP64 ? (size_t)16 * P.ldl * 2 : 8));  // Ylp
+        const R3Plan* r3 = pl.r3.get();
+        v.push_back(ar.add(r3 ? r3_bmat_bytes(*r3, P.TP, P.n) : 8));              // rung-3 operands
+        v.push_back(ar.add(r3 ? r3_pstat_bytes(*r3, P.TP) : 8));                  // partner ranges, sums
     }
     char* base = (char*)ctx->raw("scr_arena", ar.total);
     char* obase = (char*)ctx->raw("scr_ops" + ctx->ops_tag, ao.total);
@@ -2782,6 +2485,8 @@ static void layout_problems(discover_ctx* ctx, const discover_problem* probs, in
         double* r2q = (double*)at();
         if (P.plan->sp.stream3) { P.r2v = r2v; P.r2m = r2m; P.r2q = r2q; }
         P.ylp = at();
+        P.r3b = (double*)at();
+        P.r3p = (double*)at();
     }
 }
 
@@ -3066,31 +2771,16 @@ static void screen_all(discover_ctx* ctx, const discover_problem* probs, int nb,
         const Plan& pl = *P.plan;
         const Space& sp = pl.sp;
         const SpaceDev& sd = sp.d;
-        if (!sp.stream3 || !pl.r3_ops || !pl.n_r3tiles) continue;
-        R3Args g3{};
-        g3.tiles = pl.r3tiles; g3.klist = pl.ilist; g3.n_tiles = pl.n_r3tiles;
-        g3.n = P.n; g3.ldm = P.ldm; g3.ldn = P.ldn; g3.Mc = P.Mc;
-        g3.c1_lo = sp.rung_start[1]; g3.c1_hi = sp.rung_start[2];
-        g3.pe = sp.rung_start[sd.pool[3] + 1];
-        g3.B = sp.B;
-        g3.Vs = P.Vs; g3.Rs = P.Rs; g3.Cs = P.Cs; g3.Vf = P.Vf; g3.Rf = P.Rf; g3.Cf = P.Cf;
-        g3.mu = P.mu; g3.mur = P.mur; g3.valid = P.valid; g3.mat_raw = pl.mat_raw;
-        g3.mat_unit = pl.mat_unit; g3.r2v = P.r2v; g3.r2m = P.r2m; g3.r2q = P.r2q; g3.msq = P.msq;
-        g3.Yn = P.Yn; g3.ysum = P.ysum; g3.T = P.T; g3.mode = prm.score_mode;
-        g3.opmask = pl.r3_ops; g3.sd = sd; g3.N = P.N; g3.scores = P.scores; g3.nscored = P.ctr + 2;
-        g3.fix_cap = P.fix_cap; g3.fix_ids = P.fix_ids3; g3.fix_cnt = P.ctr + 3;
-        {
-            KTimer kt(ctx, st, "screen_r3");
-            const unsigned blocks = (unsigned)cdiv(g3.n_tiles, 4);
-            switch (P.TP) {
-            case 1: k_screen_r3<31, 2, 1><<<blocks, 256, 0, st>>>(g3); break;
-            case 2: k_screen_r3<31, 2, 2><<<blocks, 256, 0, st>>>(g3); break;
-            case 4: k_screen_r3<31, 1, 4><<<blocks, 256, 0, st>>>(g3); break;
-            case 8: k_screen_r3<31, 1, 8><<<blocks, 256, 0, st>>>(g3); break;
-            default: k_screen_r3<31, 1, 16><<<blocks, 256, 0, st>>>(g3); break;
-            }
-            check_launch("k_screen_r3");
-        }
+        if (!sp.stream3 || !pl.r3_ops || !pl.r3) continue;
+        R3Launch g3{};
+        g3.plan = pl.r3.get();
+        g3.n = P.n; g3.ldn = P.ldn; g3.TP = P.TP; g3.T = P.T; g3.mode = prm.score_mode;
+        g3.Vf = P.Vf; g3.Rf = P.Rf; g3.Cf = P.Cf; g3.mu = P.mu; g3.msq = P.msq;
+        g3.valid = P.valid; g3.mat_raw = pl.mat_raw; g3.Yn = P.Yn; g3.ysum = P.ysum;
+        g3.r2v = P.r2v; g3.r2m = P.r2m; g3.r2q = P.r2q; g3.sd = sd; g3.N = P.N;
+        g3.scores = P.scores; g3.nscored = P.ctr + 2; g3.fix_ids = P.fix_ids3;
+        g3.fix_cnt = P.ctr + 3; g3.fix_cap = P.fix_cap; g3.bmat = P.r3b; g3.pstat = P.r3p;
+        launch_r3(ctx, g3, st);
         FixArgs a = fa[b];
         a.ids = P.fix_ids3; a.cnt = P.ctr + 3; a.r2v = nullptr; a.r2m = nullptr; a.r2q = nullptr;
         fa3.push_back(a);
