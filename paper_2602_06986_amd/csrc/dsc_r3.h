@@ -49,8 +49,16 @@ std::shared_ptr<R3Plan> build_r3_plan(const Space& sp, uint32_t r3_ops);
 
 // Per-call buffers of one problem's rung-3 screen.
 inline int r3_quads(int n) { return 4 * (int)((n + 15) / 16); }
+inline int r3_chunks(int n) { return (int)((n + 31) / 32); }
+// The main tiles' operands (FP64 layout, or the precision form's), then the
+// add/sub tiles' (FP64 layout) at r3_as_offset bytes.
+inline size_t r3_as_offset(const R3Plan& p, int TP, int n) {
+    const size_t f64 = (size_t)p.n_ctiles * (TP + 2) * r3_quads(n) * 64 * 8;
+    const size_t lp = (size_t)p.n_ctiles * r3_chunks(n) * 512 * (2 * 8 + TP * 2);
+    return (std::max(f64, lp) + 255) & ~(size_t)255;
+}
 inline size_t r3_bmat_bytes(const R3Plan& p, int TP, int n) {
-    return (size_t)(p.n_ctiles + p.n_as_ctiles) * (TP + 2) * r3_quads(n) * 64 * 8;
+    return r3_as_offset(p, TP, n) + (size_t)p.n_as_ctiles * (TP + 2) * r3_quads(n) * 64 * 8;
 }
 inline size_t r3_pstat_bytes(const R3Plan& p, int TP) {
     return (size_t)std::max(p.pe, 1) * (2 + TP + 2) * 8;
@@ -72,6 +80,8 @@ struct R3Launch {
     int64_t* fix_ids;
     unsigned long long* fix_cnt;
     int64_t fix_cap;
+    int precision;                    // DISCOVER_BF16_GUARD: precision form of mul/div/rdiv
+    double delta;                     // its error bound per unit sqrt(kappa)
     double* bmat;                     // r3_bmat_bytes
     double* pstat;                    // r3_pstat_bytes: max |x|, min |x| per partner,
                                       // then the add/sub partner sums

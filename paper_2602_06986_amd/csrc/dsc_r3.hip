@@ -446,6 +446,233 @@ __global__ __launch_bounds__(256) void k_r3_mm(R3mArgs g) {
     if (lane == 0 && cnt) atomicAdd(g.nscored, (unsigned long long)cnt);
 }
 
+// ------------------------------------------------------------ precision form
+// BF16 numerators, FP64 moments.  Per 32-sample chunk a lane regenerates 8
+// consecutive samples of its row (rows 16 rung-2 features, as above).  S1
+// and S2 come from 8 + 8 FP64 MFMAs against [x | x^2] (sample 8(l/16) + q of
+// the chunk in MFMA q); the T numerators from one v_mfma_f32_16x16x32_bf16
+// each against x y_t rounded to BF16 (lane l supplies row l%16 at samples
+// 8(l/16)..+7 and column l%16 at the same samples, and receives
+// D[4(l/16)+e][l%16]).  The FP64 results are moved to the FP32 layout by
+// register shuffles before the epilogue.
+//
+// Error: with u = 2^-8 (plus the FP64 -> FP32 -> BF16 double rounding) the
+// product of two rounded values is within 2u + u^2 of the true product and
+// the FP32 sum adds gamma_n, so |P_lp - P| <= delta ||f|| ||y_t|| and
+// |r_lp - r| <= delta sqrt(kappa) with kappa = S2 / (S2 - S1^2/n): delta is
+// the precision form's BF16 bound.  Scores with kappa <= LP_KAPPA are stored
+// (error within the selection margin); others store the upper bound
+// -(s + delta sqrt(kappa) + FP64 error) and are rescored exactly when they
+// can reach the pool.  Rows or partners whose values leave a safe FP32 range
+// (products above LP_BIG, or a norm below LP_SMALL where subnormals would
+// matter) go to the exact fix-up.
+constexpr double LP_BIG = 1e30;
+constexpr double LP_SMALL = 1e-20;
+constexpr double LP_KAPPA = 1.21;
+
+typedef __attribute__((ext_vector_type(8))) __bf16 r3_bf16x8;
+typedef __attribute__((ext_vector_type(4))) float r3_f32x4;
+typedef __attribute__((ext_vector_type(4))) unsigned r3_u32x4;
+
+// Two FP32 values rounded to BF16 (nearest, ties to even) and packed, with
+// plain integer operations: lo in bits 0..15, hi in bits 16..31 (finite
+// inputs; the rounding is explicit and identical in the layout kernel and
+// the screen).
+__device__ __forceinline__ unsigned r3_bf16_pack(float lo, float hi) {
+    unsigned a = __float_as_uint(lo), b = __float_as_uint(hi);
+    a += 0x7FFFu + ((a >> 16) & 1u);
+    b += 0x7FFFu + ((b >> 16) & 1u);
+    return (a >> 16) | (b & 0xFFFF0000u);
+}
+
+// Right-hand operands of the precision form: b64[((c 2 + v) NC + ch) 512 +
+// 8 l + e] = x (v = 0) or x^2 (v = 1) of column l%16 at sample 32 ch +
+// 8 (l/16) + e; blp[((c TP + t) NC + ch) 512 + 8 l + e] = BF16(x y_t) there.
+__global__ __launch_bounds__(256) void k_r3_bmat_lp(int n, int64_t ldn, int TP, int NC, int nct,
+                                                    const int32_t* __restrict__ coldesc,
+                                                    const double* __restrict__ Vf, const double* __restrict__ Rf,
+                                                    const double* __restrict__ Yn, double* __restrict__ b64,
+                                                    __bf16* __restrict__ blp) {
+    const int64_t per = (int64_t)NC * 512;
+    const int64_t total = (int64_t)nct * (2 + TP) * per;
+    for (int64_t f = (int64_t)blockIdx.x * 256 + threadIdx.x; f < total; f += (int64_t)gridDim.x * 256) {
+        const int64_t r = f % per, ck = f / per;
+        const int c = (int)(ck / (2 + TP)), v = (int)(ck % (2 + TP));
+        const int ch = (int)(r / 512), l = (int)((r % 512) / 8), e = (int)(r % 8);
+        const int j = l & 15, s = 32 * ch + 8 * (l >> 4) + e;
+        const int32_t d = coldesc[c * 16 + j];
+        double x = 0.0;
+        if (d >= 0 && s < n) {
+            const int p = d & 0xFFFF, kind = d >> 16;
+            x = kind == 3 ? 1.0 : kind == 1 ? Rf[(int64_t)p * ldn + s] : Vf[(int64_t)p * ldn + s];
+        }
+        if (v < 2) {
+            b64[((int64_t)c * 2 + v) * per + r] = v == 0 ? x : x * x;
+        } else {
+            const int t = v - 2;
+            const double yv = (s < n) ? Yn[(int64_t)t * ldn + s] : 0.0;
+            const unsigned pk = r3_bf16_pack((float)(x * yv), 0.0f);
+            blp[((int64_t)c * TP + t) * per + r] = __builtin_bit_cast(__bf16, (unsigned short)(pk & 0xFFFFu));
+        }
+    }
+}
+
+struct R3lpArgs {
+    R3mArgs m;
+    const double* b64;
+    const __bf16* blp;
+    int NC;
+    double delta;
+};
+
+template <int TP>
+__global__ __launch_bounds__(256) void k_r3_lp(R3lpArgs a) {
+    const R3mArgs& g = a.m;
+    const int lane = threadIdx.x & 63;
+    const int r16 = lane & 15, kq = lane >> 4;
+    const int ct = blockIdx.x / g.n_gblk;
+    const int64_t tile0 = (int64_t)(blockIdx.x - ct * g.n_gblk) * 4 + r3_wave();
+    if (tile0 * 16 >= g.n_grec) return;
+    const bool hk = ct >= g.n_gct;
+    int k = -2, l = 0, op2;
+    const int64_t rec = tile0 * 16 + r16;
+    r3_rec(g.grec[rec < g.n_grec ? rec : tile0 * 16], k, l, op2);
+    op2 = __builtin_amdgcn_readfirstlane(op2);
+    bool rok = rec < g.n_grec && k != -2;
+    const int64_t j2 = rok ? r3_j2(g.sd, g.mat_raw, k, l, op2) : 0;
+    rok = rok && g.r2v[j2 - g.sd.off[2]];
+    const double* p1;
+    const double* p2;
+    r3_rows(g.Vf, g.Rf, g.ldn, op2 < OP_ADD ? -1 : (rok ? k : 0), rok ? l : 0, op2, p1, p2);
+
+    r3_v4d s1 = {0.0, 0.0, 0.0, 0.0}, s2 = {0.0, 0.0, 0.0, 0.0};
+    r3_f32x4 pa[TP];
+#pragma unroll
+    for (int t = 0; t < TP; t++) pa[t] = r3_f32x4{0.f, 0.f, 0.f, 0.f};
+    double gmx = 0.0, gmn = INFINITY;
+    const double* b1p = a.b64 + ((int64_t)ct * 2 * a.NC) * 512 + lane * 8;
+    const double* b2p = b1p + (int64_t)a.NC * 512;
+    const __bf16* bl = a.blp + ((int64_t)ct * TP * a.NC) * 512 + lane * 8;
+    for (int ch = 0; ch < a.NC; ch++) {
+        const int s = 32 * ch + 8 * kq;
+        double v[8];
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const r3_v4d w = r3_combine(op2, *(const r3_v4d*)(p1 + s + 4 * h), *(const r3_v4d*)(p2 + s + 4 * h));
+#pragma unroll
+            for (int e = 0; e < 4; e++) v[4 * h + e] = w[e];
+        }
+        float vf[8];
+#pragma unroll
+        for (int e = 0; e < 8; e++) {
+            const bool in = rok && s + e < g.n;
+            double x = in ? v[e] : 0.0;
+            if (in) {
+                gmx = fmax(gmx, fabs(x));
+                gmn = fmin(gmn, fabs(x));
+            }
+            if (hk) x = in ? r3_rcp(x) : 0.0;
+            v[e] = x;
+            vf[e] = (float)x;
+        }
+        const r3_v4d b1a = *(const r3_v4d*)(b1p + (int64_t)ch * 512), b1b = *(const r3_v4d*)(b1p + (int64_t)ch * 512 + 4);
+        const r3_v4d b2a = *(const r3_v4d*)(b2p + (int64_t)ch * 512), b2b = *(const r3_v4d*)(b2p + (int64_t)ch * 512 + 4);
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            s1 = __builtin_amdgcn_mfma_f64_16x16x4f64(v[q], b1a[q], s1, 0, 0, 0);
+            s2 = __builtin_amdgcn_mfma_f64_16x16x4f64(v[q] * v[q], b2a[q], s2, 0, 0, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            s1 = __builtin_amdgcn_mfma_f64_16x16x4f64(v[4 + q], b1b[q], s1, 0, 0, 0);
+            s2 = __builtin_amdgcn_mfma_f64_16x16x4f64(v[4 + q] * v[4 + q], b2b[q], s2, 0, 0, 0);
+        }
+        const r3_u32x4 au = {r3_bf16_pack(vf[0], vf[1]), r3_bf16_pack(vf[2], vf[3]),
+                             r3_bf16_pack(vf[4], vf[5]), r3_bf16_pack(vf[6], vf[7])};
+        const r3_bf16x8 av = __builtin_bit_cast(r3_bf16x8, au);
+#pragma unroll
+        for (int t = 0; t < TP; t++) {
+            const r3_bf16x8 bv = *(const r3_bf16x8*)(bl + ((int64_t)t * a.NC + ch) * 512);
+            pa[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, pa[t], 0, 0, 0);
+        }
+    }
+    gmx = fmax(gmx, __shfl_xor(gmx, 16, 64));
+    gmx = fmax(gmx, __shfl_xor(gmx, 32, 64));
+    gmn = fmin(gmn, __shfl_xor(gmn, 16, 64));
+    gmn = fmin(gmn, __shfl_xor(gmn, 32, 64));
+    // FP64 results: row kq + 4r in register r; wanted: row 4 kq + e in slot e
+    double S1[4], S2[4];
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+        S1[e] = 0.0;
+        S2[e] = 0.0;
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const double x1 = __shfl(s1[r], r16 + 16 * e, 64), x2 = __shfl(s2[r], r16 + 16 * e, 64);
+            if (r == kq) { S1[e] = x1; S2[e] = x2; }
+        }
+    }
+    const int32_t cd = g.coldesc[ct * 16 + r16];
+    const int p = cd & 0xFFFF, kind = cd >> 16;
+    const int op3 = kind == 0 ? OP_MUL : kind == 1 ? OP_RDIV : OP_DIV;
+    const bool colok = cd >= 0 && ((g.ops >> (op3 - OP_ADD)) & 1u) && g.valid[p];
+    const double xmx = colok ? g.pstat[p] : 0.0, xmn = colok ? g.pstat[g.pe + p] : 1.0;
+    const int64_t praw = colok ? g.mat_raw[p] : 0;
+    const double nn = (double)g.n;
+    unsigned cnt = 0;
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+        const int i = 4 * kq + e;                          // row of slot e
+        const bool ok = __shfl((int)rok, i, 64) != 0 && colok;
+        const int64_t gj = __shfl(j2, i, 64);
+        const double rmx = __shfl(gmx, i, 64), rmn = __shfl(gmn, i, 64);
+        if (!ok) continue;
+        const int64_t id = pair_id(g.sd, 3, op3, praw, gj);
+        bool sure;
+        double amx, fmx, bmx;                              // largest |A|, |f|, |B| of the products
+        if (op3 == OP_MUL) {
+            sure = rmx * xmx < R3_BIG;
+            amx = rmx; fmx = rmx * xmx; bmx = xmx;
+        } else if (op3 == OP_DIV) {
+            if (rmn == 0.0) continue;                      // x / 0: not finite
+            sure = rmn >= R3_TINY && xmx < R3_BIG * rmn;
+            amx = 1.0 / rmn; fmx = xmx / rmn; bmx = xmx;
+        } else {
+            if (xmn == 0.0) continue;                      // g / 0: not finite
+            sure = xmn >= R3_TINY && rmx < R3_BIG * xmn;
+            amx = rmx; fmx = rmx / xmn; bmx = 1.0 / xmn;
+        }
+        const double varn = S2[e] - S1[e] * (S1[e] / nn);
+        const double kappa = varn > 0.0 ? S2[e] / varn : INFINITY;
+        const bool lp_ok = amx < LP_BIG && fmx < LP_BIG && bmx < LP_BIG && S2[e] > LP_SMALL * LP_SMALL;
+        if (!sure || !lp_ok || !(kappa <= R3_KAPPA_MAX)) {
+            const unsigned long long slot = r3_slot(g.fix_cnt);
+            if ((int64_t)slot < g.fix_cap) g.fix_ids[slot] = id;
+            continue;
+        }
+        const double isd = 1.0 / sqrt(varn);
+        const bool precise = kappa <= LP_KAPPA;
+        const double ub = a.delta * sqrt(kappa) + 4.0 * nn * 1.1102230246251565e-16 * kappa;
+        cnt++;
+        if (g.mode == DISCOVER_SCORE_MAX) {
+            double best = 0.0;
+#pragma unroll
+            for (int t = 0; t < TP; t++)
+                if (t < g.T) best = fmax(best, fabs(((double)pa[t][e] - S1[e] * (g.ysum[t] / nn)) * isd));
+            g.scores[id] = precise ? best : -(best + ub);
+        } else {
+#pragma unroll
+            for (int t = 0; t < TP; t++)
+                if (t < g.T) {
+                    const double r = fabs(((double)pa[t][e] - S1[e] * (g.ysum[t] / nn)) * isd);
+                    g.scores[(int64_t)t * g.N + id] = precise ? r : -(r + ub);
+                }
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor((int)cnt, o, 64);
+    if (lane == 0 && cnt) atomicAdd(g.nscored, (unsigned long long)cnt);
+}
+
 template <class T>
 T* r3_up(R3Plan& P, const std::vector<T>& v) {
     void* p = nullptr;
@@ -591,7 +818,38 @@ std::shared_ptr<R3Plan> build_r3_plan(const Space& sp, uint32_t r3_ops) {
 void launch_r3(discover_ctx* ctx, const R3Launch& a, hipStream_t st) {
     const R3Plan& P = *a.plan;
     const int NQ = r3_quads(a.n);
-    if (P.n_grec && P.n_ctiles) {
+    if (P.n_grec && P.n_ctiles && a.precision == DISCOVER_BF16_GUARD) {
+        k_r3_pstat<<<(unsigned)P.pe, 256, 0, st>>>(a.n, a.ldn, P.pe, a.Vf, a.pstat);
+        check_launch("k_r3_pstat");
+        const int NC = r3_chunks(a.n);
+        double* b64 = a.bmat;
+        __bf16* blp = (__bf16*)(a.bmat + (size_t)P.n_ctiles * 2 * NC * 512);
+        const int64_t tot = (int64_t)P.n_ctiles * (a.TP + 2) * NC * 512;
+        k_r3_bmat_lp<<<(unsigned)std::min<int64_t>(cdiv(tot, 256), 16384), 256, 0, st>>>(
+            a.n, a.ldn, a.TP, NC, P.n_ctiles, P.coldesc, a.Vf, a.Rf, a.Yn, b64, blp);
+        check_launch("k_r3_bmat_lp");
+        R3lpArgs l{};
+        R3mArgs& m = l.m;
+        m.grec = P.grec; m.n_grec = P.n_grec; m.coldesc = P.coldesc; m.n_gct = P.n_gct;
+        m.NQ = NQ; m.n = a.n; m.T = a.T; m.mode = a.mode; m.ldn = a.ldn; m.bmat = a.bmat;
+        m.Vf = a.Vf; m.Rf = a.Rf; m.pstat = a.pstat; m.pe = P.pe; m.ops = P.ops;
+        m.valid = a.valid; m.mat_raw = a.mat_raw; m.r2v = a.r2v; m.ysum = a.ysum; m.sd = a.sd;
+        m.N = a.N; m.scores = a.scores; m.nscored = a.nscored; m.fix_ids = a.fix_ids;
+        m.fix_cnt = a.fix_cnt; m.fix_cap = a.fix_cap;
+        m.n_gblk = (int)((P.n_grec / 16 + 3) / 4);
+        l.b64 = b64; l.blp = blp; l.NC = NC; l.delta = a.delta;
+        const int64_t blocks = (int64_t)m.n_gblk * P.n_ctiles;
+        DSC_REQUIRE(blocks < ((int64_t)1 << 31), "rung-3 grid too large");
+        KTimer kt(ctx, st, "screen_r3");
+        switch (a.TP) {
+        case 1: k_r3_lp<1><<<(unsigned)blocks, 256, 0, st>>>(l); break;
+        case 2: k_r3_lp<2><<<(unsigned)blocks, 256, 0, st>>>(l); break;
+        case 4: k_r3_lp<4><<<(unsigned)blocks, 256, 0, st>>>(l); break;
+        case 8: k_r3_lp<8><<<(unsigned)blocks, 256, 0, st>>>(l); break;
+        default: k_r3_lp<16><<<(unsigned)blocks, 256, 0, st>>>(l); break;
+        }
+        check_launch("k_r3_lp");
+    } else if (P.n_grec && P.n_ctiles) {
         k_r3_pstat<<<(unsigned)P.pe, 256, 0, st>>>(a.n, a.ldn, P.pe, a.Vf, a.pstat);
         check_launch("k_r3_pstat");
         const int64_t tot = (int64_t)P.n_ctiles * (a.TP + 2) * NQ * 64;
@@ -619,7 +877,7 @@ void launch_r3(discover_ctx* ctx, const R3Launch& a, hipStream_t st) {
         check_launch("k_r3_mm");
     }
     if (P.n_as_work) {
-        double* bm = a.bmat + (size_t)P.n_ctiles * (a.TP + 2) * NQ * 64;
+        double* bm = (double*)((char*)a.bmat + r3_as_offset(P, a.TP, a.n));
         double* pc = a.pstat + 2 * P.pe;
         k_r3_pconst<<<(unsigned)P.pe, 256, 0, st>>>(a.n, a.ldn, a.TP, a.Vf, a.Yn, pc);
         check_launch("k_r3_pconst");

@@ -2780,6 +2780,10 @@ static void screen_all(discover_ctx* ctx, const discover_problem* probs, int nb,
         g3.r2v = P.r2v; g3.r2m = P.r2m; g3.r2q = P.r2q; g3.sd = sd; g3.N = P.N;
         g3.scores = P.scores; g3.nscored = P.ctr + 2; g3.fix_ids = P.fix_ids3;
         g3.fix_cnt = P.ctr + 3; g3.fix_cap = P.fix_cap; g3.bmat = P.r3b; g3.pstat = P.r3p;
+        // the precision form covers rung 3 in BF16 (FP16's range would need
+        // per-row scaling; the FP16 form keeps rung 3 in FP64)
+        g3.precision = prm.precision;
+        g3.delta = prm.precision == DISCOVER_BF16_GUARD ? lowprec_delta(prm.precision, P.n) : 0.0;
         launch_r3(ctx, g3, st);
         FixArgs a = fa[b];
         a.ids = P.fix_ids3; a.cnt = P.ctr + 3; a.r2v = nullptr; a.r2m = nullptr; a.r2q = nullptr;

@@ -402,11 +402,16 @@ def test_precision_max_mode(torch, ctx, D, oracle_mod, prec, T, B, rung):
 
 
 # ------------------------------------------------------- operator-limited rung 3
-@pytest.mark.parametrize("seed,p,n,B,T,mode", [(0, 4, 61, 0, 1, "per_target"), (1, 5, 130, 2, 1, "per_target"),
-                                               (2, 4, 97, 0, 3, "max"), (3, 5, 64, 3, 2, "max")])
-def test_screen_rung3_limited(torch, ctx, D, oracle_mod, seed, p, n, B, T, mode):
+@pytest.mark.parametrize("seed,p,n,B,T,mode,prec", [
+    (0, 4, 61, 0, 1, "per_target", "fp64"), (1, 5, 130, 2, 1, "per_target", "fp64"),
+    (2, 4, 97, 0, 3, "max", "fp64"), (3, 5, 64, 3, 2, "max", "fp64"),
+    (4, 5, 130, 2, 1, "per_target", "bf16"), (5, 4, 97, 0, 3, "max", "bf16"),
+    (6, 6, 200, 3, 8, "max", "bf16"), (7, 4, 33, 0, 5, "per_target", "bf16")])
+def test_screen_rung3_limited(torch, ctx, D, oracle_mod, seed, p, n, B, T, mode, prec):
     """Rung 3 restricted to binary operators with a primary partner: the
-    rung-2 operand of every rung-3 candidate is regenerated on the fly."""
+    rung-2 operand of every rung-3 candidate is regenerated on the fly (FP64
+    matrix products, or the BF16 precision form with its exact rescoring of
+    the guard band)."""
     O = oracle_mod
     rng = np.random.default_rng(300 + seed)
     X = rng.lognormal(0, 0.4, size=(p, n))
@@ -419,8 +424,11 @@ def test_screen_rung3_limited(torch, ctx, D, oracle_mod, seed, p, n, B, T, mode)
     sp = O.Space(p, 3, O.OPS, rung_ops, rung_pool)
     lists, status, nvalid = O.sis(sp, X, units, Y, 30, (), mode)
     q = D.params(rung=3, k=30, rung_ops=rung_ops, rung_pool=rung_pool,
-                 score_mode=D.SCORE_MAX if mode == "max" else D.SCORE_PER_TARGET)
+                 score_mode=D.SCORE_MAX if mode == "max" else D.SCORE_PER_TARGET,
+                 precision=D.BF16_GUARD if prec == "bf16" else D.FP64)
     ids, sc, vals, st = ctx.generate_screen(dev(torch, X), dev(torch, Y), q, units=units)
+    if prec == "bf16":
+        assert st["max_lowprec_err"] <= st["guard_band"]
     for t, (li, ls, _) in enumerate(lists):
         check_selection(ids[t].cpu().numpy(), sc[t].cpu().numpy(), li, ls, what="r3 list %d" % t)
     assert st["n_raw"] == sp.N
