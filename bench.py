@@ -1,15 +1,20 @@
-"""Benchmark of the MI355X hot path on the 16-feature unit workload.
+"""Benchmark of the MI355X hot path on the large workload (default).
 
 One step = one full pass of the method over one synthetic dataset resident
-in HBM (n = 500 samples, p = 16 lognormal(0, 0.5) primaries over 3 base
-units, rung 2): for d = 1, 2, 3 generate + unit-prune + screen every
-candidate against the current residual and select the exact top-500, then
-exhaustive L0 over all d-subsets of the union subspace (500 / 1000 / 1500
-features) with QR refit of the band; finally OMP from the 3-term winner to
-6 terms.  The step is one replay of the hipGraph that discover_sisso_batch
-captures of this whole sequence; the eager per-call loop is timed beside it.
+in HBM: n = 2000 samples, p = 24 lognormal(0, 0.5) primaries over 3 base
+units, rung 2 plus an operator-limited rung 3 (702,860,274 raw / 118,424,801
+unit-valid candidates per dimension).  For d = 1, 2, 3 every candidate is
+generated, unit-pruned and screened (against y at d = 1, then against the 8
+residuals of the best 8 models of d - 1, max score) in the BF16 precision
+form with exact FP64 rescoring of its guard band, the exact top-1000 is
+selected, and exhaustive L0 in FP64 fits y over all d-subsets of the union
+subspace (1000 / 2000 / 3000 features); finally OMP extends the 3-term
+winner to 6 terms.  The step is one replay of the hipGraph that
+discover_sisso_batch captures of this whole sequence.  The same step with
+FP64 screening is timed beside it; both must select identically and match
+the stored FP64 oracle reference (tests/golden/large24.json).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload large24|units16|batch128]
 
 Prints one JSON line.  `value` = (unit-valid candidates screened + L0
 subsets fitted) per second of whole-step time on one GPU.
@@ -38,6 +43,11 @@ SWEEP3_COUNTERS = {
 }
 
 
+# HBM counters of the rung-3 kernels on this workload (per launch-average),
+# filled from rocprofv3 passes of the committed source (see profiles/).
+R3_COUNTERS = {}
+
+
 def sweep3_traffic():
     """Scaled counter bytes per launch, or None once the kernel source differs."""
     import hashlib
@@ -56,11 +66,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="units16", choices=("units16", "batch128", "large24"),
-                    help="units16 (default): one 16-feature unit dataset; batch128: 128 datasets "
-                         "of uneven size, plain per-dataset loop vs batched vs graph-replayed; "
-                         "large24: 24 features with units, rung 2 + operator-limited rung 3, "
-                         "8 residuals, top-1000, L0 D<=3, OMP to 6, FP64 vs BF16/FP16 screening")
+    ap.add_argument("--workload", default="large24", choices=("units16", "batch128", "large24"),
+                    help="large24 (default): 24 features with units, rung 2 + operator-limited "
+                         "rung 3, 8 residuals, top-1000, L0 D<=3, OMP to 6, BF16 vs FP64 "
+                         "screening; units16: one 16-feature unit dataset; batch128: 128 "
+                         "datasets of uneven size, plain per-dataset loop vs batched vs "
+                         "graph-replayed")
     ap.add_argument("--no-oracle", action="store_true", help="skip the parity gate and CPU baseline")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device-to-device copy of MIB MiB (the reference "
@@ -194,14 +205,144 @@ def batch_main(args):
     print(json.dumps(line))
 
 
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+S_RTOL = 1e-10      # scores and RMSE, relative (FP64 rounding of two-pass moments and QR)
+TIE = 1e-12         # near-tie at the cut: either member is a correct selection
+
+
+def load_golden(name):
+    path = os.path.join(GOLDEN, name)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f)
+
+
+def check_against_golden(gold, sel, models, omp, y, counts=None):
+    """Compare one dataset's GPU results with a stored oracle reference.
+    sel[d] = (ids, scores) in (-score, ID) order; models[d] = list of
+    (sorted candidate IDs, rmse, coef with the intercept first and the rest in
+    ID order); omp = (ids in order of addition, rmse) or None; counts[d] =
+    (n_scored, n_unit_valid) or None.  Returns (ok, list of mismatches)."""
+    import numpy as np
+    bad = []
+    ystd = float(np.std(y))
+    for d, gd in enumerate(gold["dims"]):
+        g_ids = [int(v) for v in sel[d][0] if v >= 0]
+        g_sc = dict(zip(g_ids, [float(v) for v in sel[d][1][:len(g_ids)]]))
+        o_sc = dict(zip(gd["sel_ids"], gd["sel_scores"]))
+        if len(g_ids) != len(gd["sel_ids"]):
+            bad.append("d%d: %d selected vs %d" % (d + 1, len(g_ids), len(gd["sel_ids"])))
+        sk = min(gd["sel_scores"]) if gd["sel_scores"] else 0.0
+        for i in set(gd["sel_ids"]) - set(g_ids):       # only documented near-ties may differ
+            if not o_sc[i] <= sk * (1 + TIE):
+                bad.append("d%d: missing %d" % (d + 1, i))
+        for i in set(g_ids) - set(gd["sel_ids"]):
+            if not abs(g_sc[i] - sk) <= 10 * TIE * sk:
+                bad.append("d%d: extra %d" % (d + 1, i))
+        for i in set(g_ids) & set(gd["sel_ids"]):
+            if not abs(g_sc[i] - o_sc[i]) <= S_RTOL * o_sc[i]:
+                bad.append("d%d: score of %d %r vs %r" % (d + 1, i, g_sc[i], o_sc[i]))
+        if counts is not None and counts[d] is not None:
+            if counts[d] != (gd["n_valid"], gd["n_unit_valid"]):
+                bad.append("d%d: counts %s vs %s" % (d + 1, counts[d], (gd["n_valid"], gd["n_unit_valid"])))
+        for q, mo in enumerate(gd["models"]):
+            if q >= len(models[d]):
+                bad.append("d%d: model %d absent" % (d + 1, q))
+                continue
+            ids_g, rmse_g, coef_g = models[d][q]
+            order = np.argsort(mo["ids"])
+            if list(ids_g) != sorted(mo["ids"]):
+                bad.append("d%d model %d: %s vs %s" % (d + 1, q, list(ids_g), sorted(mo["ids"])))
+                continue
+            if not abs(rmse_g - mo["rmse"]) <= S_RTOL * mo["rmse"] + 1e-13 * ystd:
+                bad.append("d%d model %d: rmse %r vs %r" % (d + 1, q, rmse_g, mo["rmse"]))
+            co = np.concatenate([[mo["coef"][0]], np.asarray(mo["coef"][1:])[order]])
+            if not np.max(np.abs(np.asarray(coef_g) - co)) <= S_RTOL * np.max(np.abs(co)):
+                bad.append("d%d model %d: coefficients" % (d + 1, q))
+    if omp is not None and "omp" in gold:
+        if list(omp[0]) != gold["omp"]["ids"]:
+            bad.append("omp: %s vs %s" % (list(omp[0]), gold["omp"]["ids"]))
+        elif not abs(omp[1] - gold["omp"]["rmse"]) <= S_RTOL * gold["omp"]["rmse"] + 1e-13 * ystd:
+            bad.append("omp rmse %r vs %r" % (omp[1], gold["omp"]["rmse"]))
+    return not bad, bad
+
+
+def graph_results(out, S_from_ids=True):
+    """Per-dimension selections and models of a one-dataset
+    discover_sisso_batch result, in the form check_against_golden takes."""
+    import numpy as np
+    ids, sc, sub, rmse, coef = (t[0].cpu().numpy() for t in out[:5])
+    D = ids.shape[0]
+    S = ids.reshape(-1)
+    sel = [(ids[d], sc[d]) for d in range(D)]
+    models = []
+    for d in range(D):
+        md = []
+        for q in range(sub.shape[1]):
+            rows = sub[d, q, :d + 1]
+            if (rows < 0).any():
+                continue
+            cid = [int(S[r]) for r in rows]
+            o = np.argsort(cid)
+            c = coef[d, q, :d + 2]
+            md.append((sorted(cid), float(rmse[d, q]), np.concatenate([[c[0]], c[1:][o]])))
+        models.append(md)
+    omp = None
+    if len(out) > 6:
+        act, oc, orm = out[6]
+        omp = ([int(S[r]) for r in act[0].cpu().numpy()], float(orm[0]))
+    return sel, models, omp
+
+
+def large_cpu_baseline(w, gold):
+    """The oracle as it stands, timed on this host on a bounded sample of
+    the same workload, extrapolated to one step by per-item time: rung-3
+    screening (the streamed oracle over a run of rung-2 operands and all
+    their rung-3 children, against 1 target and against 8) and its L0 scan
+    at this size (Gram mode with QR refits of the band) over a 400-row
+    sample of the dimension-3 subspace."""
+    import numpy as np
+    from oracle import oracle as O
+    sp = O.Space.of(w)
+    X, units = w["X"], w["units"]
+    rng = np.random.default_rng(11)
+    y = w["Y"][0]
+    Y8 = y[None, :] + 0.1 * np.std(y) * rng.normal(size=(8, w["n"]))
+    j0, J = 3_000_000, 1200
+    per = {}
+    for T, Y in ((1, y[None, :]), (8, Y8)):
+        t0 = time.perf_counter()
+        _, _, _, counts = O.screen_scores(sp, X, Y, units, "max", j_range=(j0, j0 + J))
+        dt = time.perf_counter() - t0
+        per[T] = (dt / float(counts.sum() - counts[O.ST_UNIT]), int(counts.sum() - counts[O.ST_UNIT]), dt)
+    S_ids = np.asarray(gold["S_ids"], np.int64) if gold else None
+    rows = S_ids[np.sort(rng.choice(len(S_ids), 400, replace=False))] if S_ids is not None else None
+    F, _ = O.values(sp, X, units, rows)
+    t0 = time.perf_counter()
+    O.l0(F, rows, y, 3, m=w["n_resid"], mode="gram")
+    t_l0 = time.perf_counter() - t0
+    sub_per = t_l0 / math.comb(400, 3)
+    n_cand = 118424801
+    n_sub = sum(math.comb(d * w["k"], d) for d in (1, 2, 3))
+    est = per[1][0] * n_cand + per[8][0] * 2 * n_cand + sub_per * n_sub
+    return {"value": (3 * n_cand + n_sub) / est, "unit": "items/s", "cores": int(O.lib().or_max_threads()),
+            "kind": "oracle",
+            "sample": "FP64 oracle on this host: rung-3 screening of %d unit-valid candidates (rung-2 "
+                      "operands %d..%d and their children) against 1 target (%.1f s) and 8 targets "
+                      "(%.1f s), and Gram-mode L0 with QR refits over C(400,3) = %d subsets of the "
+                      "3000-row subspace (%.1f s); one step (3 x %d candidates, %d subsets) "
+                      "extrapolated by per-item time: %.0f s"
+                      % (per[8][1], j0, j0 + J, per[1][2], per[8][2], math.comb(400, 3), t_l0,
+                         n_cand, n_sub, est)}
+
+
 def large_main(args):
-    """One step of the large configuration (n = 2000, p = 24 with units,
-    rung 2 plus an operator-limited rung 3: 702,860,274 raw candidates per
-    dimension, 8 residual targets with the max score from d = 2, SIS
-    top-1000, exhaustive L0 over the 3000-feature union, OMP to 6) with
-    plain FP64 screening and with the BF16 and FP16 precision forms; the
-    three must select identically.  value = items per second of the BF16
-    step."""
+    """One step of the large configuration as one replay of the captured
+    loop (discover_sisso_batch): BF16 precision-form screening with FP64
+    rescoring, FP64 L0 and OMP.  The same step with FP64 screening runs
+    beside it; both must select identically and match the stored oracle
+    reference.  value = items per second of the BF16 step."""
     import numpy as np
     import torch
     import synth
@@ -210,112 +351,132 @@ def large_main(args):
     w = synth.large24()
     dev = torch.device("cuda:0")
     X = torch.as_tensor(w["X"], device=dev)
-    y = torch.as_tensor(w["Y"][0], device=dev)
+    y = torch.as_tensor(w["Y"][0], device=dev).contiguous()
     ctx = Dm.Context(0)
+    D, m, omp_D = w["D"], w["n_resid"], w["omp_D"]
+    timed_kernels = ["screen_r3", "dedup_pairs", "l0_sweep3"]
+    ctx.set_graph_timing(timed_kernels)
     res = {}
-    for name, prec in (("fp64", Dm.FP64), ("bf16", Dm.BF16_GUARD), ("fp16", Dm.FP16_GUARD)):
+    for name, prec in (("fp64", Dm.FP64), ("bf16", Dm.BF16_GUARD)):
         prm = Dm.params(ops=w["ops"], rung=w["rung"], k=w["k"], rung_ops=w["rung_ops"],
                         rung_pool=w["rung_pool"], precision=prec)
 
         def step():
-            return ctx.sisso(X, y, prm, w["D"], units=w["units"], n_resid=w["n_resid"],
-                             omp_D=w["omp_D"])
-        for _ in range(args.warmup):
-            step()
+            return ctx.sisso_batch_graph([X], [y], prm, D, m=m, units=[w["units"]], omp_D=omp_D)
+        for _ in range(max(args.warmup, 2)):     # the first call runs eagerly and captures
+            out = step()
         torch.cuda.synchronize()
         ctx.set_timing(True)
         ctx.reset_timing()
+        replays = 0
         t0 = time.perf_counter()
         for _ in range(args.steps):
             out = step()
+            replays += out[5] == 1
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / args.steps
         ctx.set_timing(False)
         kern = {}
-        for kn in ("materialise", "screen_list", "screen_pairs", "screen_pairs_list", "screen_lp",
-                   "screen_r3", "screen_fixup", "select", "rescore", "sort_dedup", "dedup_pairs",
-                   "values", "l0_gram", "l0_table", "l0_sweep", "l0_sweep3", "l0_band", "l0_refit",
-                   "omp"):
+        for kn in timed_kernels:
             n, t = ctx.timing(kn)
             if n:
-                kern[kn] = {"launches_per_step": n / args.steps, "ms_per_step": t / args.steps}
-        res[name] = (dt, out, kern)
-        print("large24 %s: %.1f ms per step" % (name, dt * 1e3), file=sys.stderr, flush=True)
-    # the precision form on its own, at these shapes: the rung-2 space of the
-    # 24 features (5,810,274 raw candidates) screened against T = 8 and 16
-    # targets (max score, top-1000), FP64 vs BF16 vs FP16
-    rng = np.random.default_rng(8)
-    Xs = torch.as_tensor(w["X"], device=dev)
-    prec = {}
-    for T in (8, 16):
-        Y = torch.as_tensor(w["Y"][0][None, :] + 0.3 * rng.normal(size=(T, w["n"])) *
-                            np.std(w["Y"][0]), device=dev)
-        times, sel = {}, {}
-        for name, pr in (("fp64", Dm.FP64), ("bf16", Dm.BF16_GUARD), ("fp16", Dm.FP16_GUARD)):
-            prm = Dm.params(ops=w["ops"], rung=2, k=w["k"], score_mode=Dm.SCORE_MAX, precision=pr)
-            for _ in range(max(1, args.warmup)):
-                ids, sc, _, st = ctx.generate_screen(Xs, Y, prm, units=w["units"], values=False)
-            torch.cuda.synchronize()
-            reps = max(3, args.steps)
-            t0 = time.perf_counter()
-            for _ in range(reps):
-                ids, sc, _, st = ctx.generate_screen(Xs, Y, prm, units=w["units"], values=False)
-            torch.cuda.synchronize()
-            times[name] = (time.perf_counter() - t0) / reps * 1e3
-            sel[name] = ids.cpu().numpy()
-        prec["T%d" % T] = {"ms_fp64": times["fp64"], "ms_bf16": times["bf16"], "ms_fp16": times["fp16"],
-                           "speedup_bf16": times["fp64"] / times["bf16"],
-                           "speedup_fp16": times["fp64"] / times["fp16"],
-                           "identical": bool(np.array_equal(sel["fp64"], sel["bf16"]) and
-                                             np.array_equal(sel["fp64"], sel["fp16"]))}
-        print("precision rung 2, T=%d: %s" % (T, prec["T%d" % T]), file=sys.stderr, flush=True)
-    dt, out, kern = res["bf16"]
-    screened = sum(d["screen_stats"]["n_unit_valid"] for d in out["dims"])
-    subsets = sum(d["l0_stats"]["n_subsets"] for d in out["dims"])
-    same = True
-    ref = res["fp64"][1]
-    for name in ("bf16", "fp16"):
-        o = res[name][1]
-        same &= np.array_equal(o["S_ids"].cpu().numpy(), ref["S_ids"].cpu().numpy())
-        for a, b in zip(o["dims"], ref["dims"]):
-            same &= np.array_equal(a["subsets"].cpu().numpy(), b["subsets"].cpu().numpy())
-        same &= np.array_equal(o["omp"]["active"].cpu().numpy(), ref["omp"]["active"].cpu().numpy())
-    err = {name: max(d["screen_stats"]["max_lowprec_err"] for d in res[name][1]["dims"])
-           for name in ("bf16", "fp16")}
-    band = {name: max(d["screen_stats"]["guard_band"] for d in res[name][1]["dims"])
-            for name in ("bf16", "fp16")}
-    # dominant kernel: the rung-3 FP64 screen (8 residuals at d = 2, 3)
-    r3 = kern.get("screen_r3")
-    roof = None
-    if r3:
-        # algorithmic FP64 work: per unit-valid rung-3 candidate and sample,
-        # the operator, sum, sum of squares and T dot products: 4 + 2T flop
-        st = [d["screen_stats"] for d in out["dims"]]
-        valid3 = 116840512
-        flops = sum(valid3 * w["n"] * (4 + 2 * (1 if i == 0 else w["n_resid"])) for i in range(len(st)))
-        ach = flops / (r3["ms_per_step"] * 1e-3)
-        roof = {"kernel": "k_screen_r3 (FP64 rung-3 screen)", "bound": "alu", "achieved": ach / 1e12,
-                "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": ach / PEAK_FP64, "traffic": None}
+                kern[kn] = {"launches_per_step": n / args.steps, "ms_per_step": t / args.steps,
+                            "avg_launch_ms": t / n}
+        res[name] = (dt, graph_results(out), kern, replays)
+        print("large24 %s: %.1f ms per step, %d of %d steps replayed" % (name, dt * 1e3, replays, args.steps),
+              file=sys.stderr, flush=True)
+    # counts and stats from one eager call (the graph reports none)
+    prm_b = Dm.params(ops=w["ops"], rung=w["rung"], k=w["k"], rung_ops=w["rung_ops"],
+                      rung_pool=w["rung_pool"], precision=Dm.BF16_GUARD)
+    eager = ctx.sisso(X, y, prm_b, D, units=w["units"], n_resid=m, omp_D=omp_D)
+    stats = [d["screen_stats"] for d in eager["dims"]]
+    screened = sum(s["n_unit_valid"] for s in stats)
+    subsets = sum(math.comb(d * w["k"], d) for d in range(1, D + 1))
+    dt, (sel, models, omp), kern, replays = res["bf16"]
+    sel64, models64, omp64 = res["fp64"][1]
+    same = all(np.array_equal(a[0], b[0]) for a, b in zip(sel, sel64)) and \
+        all([x[0] for x in ma] == [x[0] for x in mb] for ma, mb in zip(models, models64)) and \
+        omp[0] == omp64[0]
+    # dominant kernel of the step: the rung-3 screen.  Algorithmic work per
+    # unit-valid rung-3 candidate and sample: the FP64 sums S1 and S2 (4 flop,
+    # on the FP64 matrix cores) in the precision form; (4 + 2T) flop for FP64
+    # screening (operator, sum, sum of squares, T products with the targets).
+    valid3 = 116840512
+    Ts = [1] + [m] * (D - 1)
+    roof = roof64 = None
+    if "screen_r3" in kern:
+        r3 = kern["screen_r3"]
+        flops = sum(valid3 * w["n"] * 4 for _ in Ts) / r3["launches_per_step"]
+        ach = flops / (r3["avg_launch_ms"] * 1e-3)
+        roof = {"kernel": "k_r3_lp (rung-3 screen, precision form)", "bound": "mfma",
+                "achieved": ach / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
+                "frac": ach / PEAK_FP64, "traffic": r3_traffic("k_r3_lp"),
+                "avg_launch_ms": r3["avg_launch_ms"], "launches_timed": r3["launches_per_step"] * args.steps,
+                "work": "4 n FP64 flop (S1, S2) per unit-valid rung-3 candidate per launch-average "
+                        "dimension; BF16 numerators (2 T n flop) not counted"}
+    if "screen_r3" in res["fp64"][2]:
+        r3 = res["fp64"][2]["screen_r3"]
+        flops = sum(valid3 * w["n"] * (4 + 2 * T) for T in Ts) / r3["launches_per_step"]
+        ach = flops / (r3["avg_launch_ms"] * 1e-3)
+        roof64 = {"kernel": "k_r3_mm (rung-3 screen, FP64)", "bound": "mfma", "achieved": ach / 1e12,
+                  "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": ach / PEAK_FP64,
+                  "traffic": r3_traffic("k_r3_mm"), "avg_launch_ms": r3["avg_launch_ms"],
+                  "work": "(4 + 2T) n FP64 flop per unit-valid rung-3 candidate, T = 1, 8, 8"}
     line = {
         "metric": "candidates screened/s + L0 subsets fitted/s, exact top-k vs FP64 oracle",
         "value": (screened + subsets) / dt, "unit": "items/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "bf16+f64", "data": "synthetic",
         "config": {"workload": "large24: n=2000, p=24 lognormal(0,0.5) over 3 base units, rung 2 + "
-                               "operator-limited rung 3 (702,860,274 raw / 118,424,801 unit-valid), "
-                               "8 residuals (max score), SIS top-1000, L0 D<=3 over 3000, OMP to 6",
-                   "candidates_screened_per_step": screened, "subsets_fitted_per_step": subsets},
-        "ms_per_step_fp64": res["fp64"][0] * 1e3, "ms_per_step_bf16": res["bf16"][0] * 1e3,
-        "ms_per_step_fp16": res["fp16"][0] * 1e3,
-        "speedup_bf16_vs_fp64": res["fp64"][0] / res["bf16"][0],
-        "speedup_fp16_vs_fp64": res["fp64"][0] / res["fp16"][0],
-        "identical_selections": bool(same), "max_lowprec_err": err, "guard_band": band,
-        "precision_form_rung2": prec,
-        "kernels_bf16": kern, "kernels_fp64": res["fp64"][2], "roofline": roof,
+                               "operator-limited rung 3 (702,860,274 raw / 118,424,801 unit-valid per "
+                               "dimension), 8 residuals (max score), SIS top-1000 (BF16 screening, FP64 "
+                               "rescoring of the guard band), L0 D<=3 over 3000 in FP64, OMP to 6",
+                   "candidates_screened_per_step": screened, "subsets_fitted_per_step": subsets,
+                   "step": "one replay of the captured loop (discover_sisso_batch)"},
+        "graph_replays": replays,
+        "ms_per_step_fp64_screening": res["fp64"][0] * 1e3,
+        "speedup_bf16_vs_fp64": res["fp64"][0] / dt,
+        "identical_selections_bf16_fp64": bool(same),
+        "max_lowprec_err": max(s["max_lowprec_err"] for s in stats),
+        "guard_band": max(s["guard_band"] for s in stats),
+        "kernels_bf16": kern, "kernels_fp64": res["fp64"][2],
+        "roofline": roof, "roofline_fp64_form": roof64,
     }
-    if not same:
+    gold = load_golden("large24.json")
+    if args.no_oracle:
+        line["parity"] = "not checked"
+    elif gold is None:
+        line["parity"] = "no reference"
         line["value"] = None
+    else:
+        counts = [(s["n_scored"], s["n_unit_valid"]) for s in stats]
+        ok, bad = check_against_golden(gold, sel, models, omp, w["Y"][0], counts)
+        ok64, bad64 = check_against_golden(gold, sel64, models64, omp64, w["Y"][0])
+        ok = ok and ok64 and same and replays == args.steps and \
+            line["max_lowprec_err"] <= line["guard_band"]
+        line["parity"] = "pass" if ok else "FAIL"
+        if not ok:
+            line["parity_mismatches"] = (bad + bad64)[:20]
+            line["value"] = None
+        line["cpu_baseline"] = large_cpu_baseline(w, gold)
     print(json.dumps(line))
+
+
+def r3_traffic(kernel):
+    """HBM bytes per launch of a rung-3 kernel from stored rocprofv3
+    FETCH_SIZE / WRITE_SIZE counters, or None when none are stored for the
+    current source of the kernel."""
+    import hashlib
+    c = R3_COUNTERS.get(kernel)
+    if not c:
+        return None
+    try:
+        with open(os.path.join(ROOT, c["source"]), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != c["sha256"]:
+                return None
+    except OSError:
+        return None
+    return (c["fetch_kib"] * c["fetch_scale"] + c["write_kib"] * c["write_scale"]) * 1024.0
 
 
 def main():
@@ -327,6 +488,13 @@ def main():
     if args.workload == "batch128":
         return batch_main(args)
     if args.workload == "large24":
+        if args.copy_calibration:
+            import torch
+            src = torch.ones(args.copy_calibration << 17, dtype=torch.float64, device="cuda:0")
+            dst = torch.empty_like(src)
+            dst.copy_(src)
+            torch.cuda.synchronize()
+            del src, dst
         return large_main(args)
     import numpy as np
     import torch

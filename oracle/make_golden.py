@@ -18,7 +18,7 @@ L0 is solved by Householder QR of every subset ("direct") wherever that is
 affordable: every dimension of units16 (5.6e8 subsets at d = 3), and
 d <= 2 elsewhere.  Where it is not (d = 3 of large24 and of the batch
 datasets), the oracle's Gram mode is used and checked against direct QR
-on (a) every subset of the Gram band of the 100 best explained fractions
+on (a) every subset of the Gram band of the 64 best explained fractions
 and (b) a seeded random sample of subsets; the check is stored with the
 reference.
 """
@@ -63,7 +63,7 @@ def model_rec(mo):
             "coef": [float(v) for v in mo["coef"]]}
 
 
-def gram_check(F, ids, y, D, models, n_top=100, n_random=200000, seed=0):
+def gram_check(F, ids, y, D, models, n_top=64, n_random=200000, seed=0):
     """Direct QR against the Gram-mode result: the band of the n_top best
     explained fractions and a random sample of subsets, each refitted by
     QR.  Returns a record; raises if QR finds a better model than the
@@ -81,6 +81,8 @@ def gram_check(F, ids, y, D, models, n_top=100, n_random=200000, seed=0):
         if cnt <= cap:
             break
         cap = int(cnt)
+    if cnt <= 0:
+        raise AssertionError("no non-singular subset in the Gram band (code %d)" % cnt)
     band = band[:cnt]
     rss_band = O.subset_rss(F, y, band)
     rng = np.random.default_rng(seed)
@@ -178,9 +180,9 @@ def main():
     elif a.which == "large24":
         w = synth.large24()
         res = sisso_record(w, ["direct", "direct", "gram"],
-                           check_gram={"n_top": 100, "n_random": 200000, "seed": 5})
+                           check_gram={"n_top": 64, "n_random": 200000, "seed": 5})
         res["note"] = ("d <= 2 by QR of every subset; d = 3 in Gram mode, checked by QR of the "
-                       "band of the 100 best explained fractions and of 200,000 random subsets")
+                       "band of the 64 best explained fractions and of 200,000 random subsets")
         write("large24.json", res)
     else:
         ws = synth.batch128()
@@ -192,10 +194,10 @@ def main():
             w = ws[b]
             print("dataset %d: n=%d p=%d" % (b, w["n"], w["p"]), flush=True)
             out.append(sisso_record(w, ["direct", "direct", "gram"],
-                                    check_gram={"n_top": 100, "n_random": 20000, "seed": b}))
+                                    check_gram={"n_top": 64, "n_random": 20000, "seed": b}))
             write("batch128.json", {"datasets": out,
                                     "note": "d <= 2 by QR of every subset; d = 3 in Gram mode, "
-                                            "checked by QR of the band of the 100 best explained "
+                                            "checked by QR of the band of the 64 best explained "
                                             "fractions and of 20,000 random subsets"})
     print("total %.0f s" % (time.time() - t0), flush=True)
 

@@ -525,92 +525,115 @@ struct R3lpArgs {
     double delta;
 };
 
-template <int TP>
+template <int TP, int GT>
 __global__ __launch_bounds__(256) void k_r3_lp(R3lpArgs a) {
     const R3mArgs& g = a.m;
     const int lane = threadIdx.x & 63;
     const int r16 = lane & 15, kq = lane >> 4;
     const int ct = blockIdx.x / g.n_gblk;
-    const int64_t tile0 = (int64_t)(blockIdx.x - ct * g.n_gblk) * 4 + r3_wave();
+    const int64_t tile0 = ((int64_t)(blockIdx.x - ct * g.n_gblk) * 4 + r3_wave()) * GT;
     if (tile0 * 16 >= g.n_grec) return;
     const bool hk = ct >= g.n_gct;
-    int k = -2, l = 0, op2;
-    const int64_t rec = tile0 * 16 + r16;
-    r3_rec(g.grec[rec < g.n_grec ? rec : tile0 * 16], k, l, op2);
-    op2 = __builtin_amdgcn_readfirstlane(op2);
-    bool rok = rec < g.n_grec && k != -2;
-    const int64_t j2 = rok ? r3_j2(g.sd, g.mat_raw, k, l, op2) : 0;
-    rok = rok && g.r2v[j2 - g.sd.off[2]];
-    const double* p1;
-    const double* p2;
-    r3_rows(g.Vf, g.Rf, g.ldn, op2 < OP_ADD ? -1 : (rok ? k : 0), rok ? l : 0, op2, p1, p2);
-
-    r3_v4d s1 = {0.0, 0.0, 0.0, 0.0}, s2 = {0.0, 0.0, 0.0, 0.0};
-    r3_f32x4 pa[TP];
+    bool rok[GT];
+    int64_t j2[GT];
+    int oo[GT];
+    const double* p1[GT];
+    const double* p2[GT];
 #pragma unroll
-    for (int t = 0; t < TP; t++) pa[t] = r3_f32x4{0.f, 0.f, 0.f, 0.f};
-    double gmx = 0.0, gmn = INFINITY;
+    for (int u = 0; u < GT; u++) {
+        const int64_t t16 = min(tile0 + u, (g.n_grec >> 4) - 1) * 16;
+        const int64_t rec = (tile0 + u) * 16 + r16;
+        int k = -2, l = 0, op2;
+        r3_rec(g.grec[rec < g.n_grec ? rec : t16], k, l, op2);
+        op2 = __builtin_amdgcn_readfirstlane(op2);
+        oo[u] = op2;
+        rok[u] = rec < g.n_grec && k != -2;
+        j2[u] = rok[u] ? r3_j2(g.sd, g.mat_raw, k, l, op2) : 0;
+        rok[u] = rok[u] && g.r2v[j2[u] - g.sd.off[2]];
+        r3_rows(g.Vf, g.Rf, g.ldn, op2 < OP_ADD ? -1 : (rok[u] ? k : 0), rok[u] ? l : 0, op2, p1[u], p2[u]);
+    }
+    r3_v4d s1[GT], s2[GT];
+    r3_f32x4 pa[GT][TP];
+    double gmx[GT], gmn[GT];
+#pragma unroll
+    for (int u = 0; u < GT; u++) {
+        s1[u] = r3_v4d{0.0, 0.0, 0.0, 0.0};
+        s2[u] = r3_v4d{0.0, 0.0, 0.0, 0.0};
+        gmx[u] = 0.0;
+        gmn[u] = INFINITY;
+#pragma unroll
+        for (int t = 0; t < TP; t++) pa[u][t] = r3_f32x4{0.f, 0.f, 0.f, 0.f};
+    }
     const double* b1p = a.b64 + ((int64_t)ct * 2 * a.NC) * 512 + lane * 8;
-    const double* b2p = b1p + (int64_t)a.NC * 512;
     const __bf16* bl = a.blp + ((int64_t)ct * TP * a.NC) * 512 + lane * 8;
+    // operands of chunk ch: the row operands (8 samples of two operand rows
+    // per tile) and the right-hand x and x y_t; the next chunk's are loaded
+    // before this chunk's products are issued
+    struct Ld {
+        r3_v4d x1[GT][2], x2[GT][2], b1[2];
+        r3_bf16x8 bv[TP];
+    };
+    auto load = [&](int ch, Ld& L) {
+        const int s = 32 * ch + 8 * kq;
+#pragma unroll
+        for (int u = 0; u < GT; u++)
+#pragma unroll
+            for (int h = 0; h < 2; h++) {
+                L.x1[u][h] = *(const r3_v4d*)(p1[u] + s + 4 * h);
+                L.x2[u][h] = *(const r3_v4d*)(p2[u] + s + 4 * h);
+            }
+        L.b1[0] = *(const r3_v4d*)(b1p + (int64_t)ch * 512);
+        L.b1[1] = *(const r3_v4d*)(b1p + (int64_t)ch * 512 + 4);
+#pragma unroll
+        for (int t = 0; t < TP; t++) L.bv[t] = *(const r3_bf16x8*)(bl + ((int64_t)t * a.NC + ch) * 512);
+    };
+    Ld cur, nxt;
+    load(0, cur);
     for (int ch = 0; ch < a.NC; ch++) {
         const int s = 32 * ch + 8 * kq;
-        double v[8];
+        load(ch + 1 < a.NC ? ch + 1 : ch, nxt);
+        const r3_v4d b1a = cur.b1[0], b1b = cur.b1[1];
+        const r3_v4d b2a = b1a * b1a, b2b = b1b * b1b;
 #pragma unroll
-        for (int h = 0; h < 2; h++) {
-            const r3_v4d w = r3_combine(op2, *(const r3_v4d*)(p1 + s + 4 * h), *(const r3_v4d*)(p2 + s + 4 * h));
+        for (int u = 0; u < GT; u++) {
+            double v[8];
 #pragma unroll
-            for (int e = 0; e < 4; e++) v[4 * h + e] = w[e];
-        }
-        float vf[8];
+            for (int h = 0; h < 2; h++) {
+                const r3_v4d w = r3_combine(oo[u], cur.x1[u][h], cur.x2[u][h]);
 #pragma unroll
-        for (int e = 0; e < 8; e++) {
-            const bool in = rok && s + e < g.n;
-            double x = in ? v[e] : 0.0;
-            if (in) {
-                gmx = fmax(gmx, fabs(x));
-                gmn = fmin(gmn, fabs(x));
+                for (int e = 0; e < 4; e++) v[4 * h + e] = w[e];
             }
-            if (hk) x = in ? r3_rcp(x) : 0.0;
-            v[e] = x;
-            vf[e] = (float)x;
-        }
-        const r3_v4d b1a = *(const r3_v4d*)(b1p + (int64_t)ch * 512), b1b = *(const r3_v4d*)(b1p + (int64_t)ch * 512 + 4);
-        const r3_v4d b2a = *(const r3_v4d*)(b2p + (int64_t)ch * 512), b2b = *(const r3_v4d*)(b2p + (int64_t)ch * 512 + 4);
+            float vf[8];
 #pragma unroll
-        for (int q = 0; q < 4; q++) {
-            s1 = __builtin_amdgcn_mfma_f64_16x16x4f64(v[q], b1a[q], s1, 0, 0, 0);
-            s2 = __builtin_amdgcn_mfma_f64_16x16x4f64(v[q] * v[q], b2a[q], s2, 0, 0, 0);
-        }
+            for (int e = 0; e < 8; e++) {
+                const bool in = rok[u] && s + e < g.n;
+                double x = in ? v[e] : 0.0;
+                if (in) {
+                    gmx[u] = fmax(gmx[u], fabs(x));
+                    gmn[u] = fmin(gmn[u], fabs(x));
+                }
+                if (hk) x = in ? r3_rcp(x) : 0.0;
+                v[e] = x;
+                vf[e] = (float)x;
+            }
 #pragma unroll
-        for (int q = 0; q < 4; q++) {
-            s1 = __builtin_amdgcn_mfma_f64_16x16x4f64(v[4 + q], b1b[q], s1, 0, 0, 0);
-            s2 = __builtin_amdgcn_mfma_f64_16x16x4f64(v[4 + q] * v[4 + q], b2b[q], s2, 0, 0, 0);
-        }
-        const r3_u32x4 au = {r3_bf16_pack(vf[0], vf[1]), r3_bf16_pack(vf[2], vf[3]),
-                             r3_bf16_pack(vf[4], vf[5]), r3_bf16_pack(vf[6], vf[7])};
-        const r3_bf16x8 av = __builtin_bit_cast(r3_bf16x8, au);
+            for (int q = 0; q < 4; q++) {
+                s1[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[q], b1a[q], s1[u], 0, 0, 0);
+                s2[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[q] * v[q], b2a[q], s2[u], 0, 0, 0);
+            }
 #pragma unroll
-        for (int t = 0; t < TP; t++) {
-            const r3_bf16x8 bv = *(const r3_bf16x8*)(bl + ((int64_t)t * a.NC + ch) * 512);
-            pa[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, pa[t], 0, 0, 0);
-        }
-    }
-    gmx = fmax(gmx, __shfl_xor(gmx, 16, 64));
-    gmx = fmax(gmx, __shfl_xor(gmx, 32, 64));
-    gmn = fmin(gmn, __shfl_xor(gmn, 16, 64));
-    gmn = fmin(gmn, __shfl_xor(gmn, 32, 64));
-    // FP64 results: row kq + 4r in register r; wanted: row 4 kq + e in slot e
-    double S1[4], S2[4];
+            for (int q = 0; q < 4; q++) {
+                s1[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[4 + q], b1b[q], s1[u], 0, 0, 0);
+                s2[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[4 + q] * v[4 + q], b2b[q], s2[u], 0, 0, 0);
+            }
+            const r3_u32x4 au = {r3_bf16_pack(vf[0], vf[1]), r3_bf16_pack(vf[2], vf[3]),
+                                 r3_bf16_pack(vf[4], vf[5]), r3_bf16_pack(vf[6], vf[7])};
+            const r3_bf16x8 av = __builtin_bit_cast(r3_bf16x8, au);
 #pragma unroll
-    for (int e = 0; e < 4; e++) {
-        S1[e] = 0.0;
-        S2[e] = 0.0;
-#pragma unroll
-        for (int r = 0; r < 4; r++) {
-            const double x1 = __shfl(s1[r], r16 + 16 * e, 64), x2 = __shfl(s2[r], r16 + 16 * e, 64);
-            if (r == kq) { S1[e] = x1; S2[e] = x2; }
+            for (int t = 0; t < TP; t++)
+                pa[u][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, cur.bv[t], pa[u][t], 0, 0, 0);
         }
+        cur = nxt;
     }
     const int32_t cd = g.coldesc[ct * 16 + r16];
     const int p = cd & 0xFFFF, kind = cd >> 16;
@@ -621,56 +644,83 @@ __global__ __launch_bounds__(256) void k_r3_lp(R3lpArgs a) {
     const double nn = (double)g.n;
     unsigned cnt = 0;
 #pragma unroll
-    for (int e = 0; e < 4; e++) {
-        const int i = 4 * kq + e;                          // row of slot e
-        const bool ok = __shfl((int)rok, i, 64) != 0 && colok;
-        const int64_t gj = __shfl(j2, i, 64);
-        const double rmx = __shfl(gmx, i, 64), rmn = __shfl(gmn, i, 64);
-        if (!ok) continue;
-        const int64_t id = pair_id(g.sd, 3, op3, praw, gj);
-        bool sure;
-        double amx, fmx, bmx;                              // largest |A|, |f|, |B| of the products
-        if (op3 == OP_MUL) {
-            sure = rmx * xmx < R3_BIG;
-            amx = rmx; fmx = rmx * xmx; bmx = xmx;
-        } else if (op3 == OP_DIV) {
-            if (rmn == 0.0) continue;                      // x / 0: not finite
-            sure = rmn >= R3_TINY && xmx < R3_BIG * rmn;
-            amx = 1.0 / rmn; fmx = xmx / rmn; bmx = xmx;
-        } else {
-            if (xmn == 0.0) continue;                      // g / 0: not finite
-            sure = xmn >= R3_TINY && rmx < R3_BIG * xmn;
-            amx = rmx; fmx = rmx / xmn; bmx = 1.0 / xmn;
-        }
-        const double varn = S2[e] - S1[e] * (S1[e] / nn);
-        const double kappa = varn > 0.0 ? S2[e] / varn : INFINITY;
-        const bool lp_ok = amx < LP_BIG && fmx < LP_BIG && bmx < LP_BIG && S2[e] > LP_SMALL * LP_SMALL;
-        if (!sure || !lp_ok || !(kappa <= R3_KAPPA_MAX)) {
-            const unsigned long long slot = r3_slot(g.fix_cnt);
-            if ((int64_t)slot < g.fix_cap) g.fix_ids[slot] = id;
-            continue;
-        }
-        const double isd = 1.0 / sqrt(varn);
-        const bool precise = kappa <= LP_KAPPA;
-        const double ub = a.delta * sqrt(kappa) + 4.0 * nn * 1.1102230246251565e-16 * kappa;
-        cnt++;
-        if (g.mode == DISCOVER_SCORE_MAX) {
-            double best = 0.0;
+    for (int u = 0; u < GT; u++) {
+        gmx[u] = fmax(gmx[u], __shfl_xor(gmx[u], 16, 64));
+        gmx[u] = fmax(gmx[u], __shfl_xor(gmx[u], 32, 64));
+        gmn[u] = fmin(gmn[u], __shfl_xor(gmn[u], 16, 64));
+        gmn[u] = fmin(gmn[u], __shfl_xor(gmn[u], 32, 64));
+        // FP64 results: row kq + 4r in register r; wanted: row 4 kq + e in slot e
+        double S1[4], S2[4];
 #pragma unroll
-            for (int t = 0; t < TP; t++)
-                if (t < g.T) best = fmax(best, fabs(((double)pa[t][e] - S1[e] * (g.ysum[t] / nn)) * isd));
-            g.scores[id] = precise ? best : -(best + ub);
-        } else {
+        for (int e = 0; e < 4; e++) {
+            S1[e] = 0.0;
+            S2[e] = 0.0;
 #pragma unroll
-            for (int t = 0; t < TP; t++)
-                if (t < g.T) {
-                    const double r = fabs(((double)pa[t][e] - S1[e] * (g.ysum[t] / nn)) * isd);
-                    g.scores[(int64_t)t * g.N + id] = precise ? r : -(r + ub);
-                }
+            for (int r = 0; r < 4; r++) {
+                const double x1 = __shfl(s1[u][r], r16 + 16 * e, 64), x2 = __shfl(s2[u][r], r16 + 16 * e, 64);
+                if (r == kq) { S1[e] = x1; S2[e] = x2; }
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            const int i = 4 * kq + e;                      // row of slot e
+            const bool ok = __shfl((int)rok[u], i, 64) != 0 && colok;
+            const int64_t gj = __shfl(j2[u], i, 64);
+            const double rmx = __shfl(gmx[u], i, 64), rmn = __shfl(gmn[u], i, 64);
+            if (!ok) continue;
+            const int64_t id = pair_id(g.sd, 3, op3, praw, gj);
+            bool sure;
+            double amx, fmx, bmx;                          // largest |A|, |f|, |B| of the products
+            if (op3 == OP_MUL) {
+                sure = rmx * xmx < R3_BIG;
+                amx = rmx; fmx = rmx * xmx; bmx = xmx;
+            } else if (op3 == OP_DIV) {
+                if (rmn == 0.0) continue;                  // x / 0: not finite
+                sure = rmn >= R3_TINY && xmx < R3_BIG * rmn;
+                amx = 1.0 / rmn; fmx = xmx / rmn; bmx = xmx;
+            } else {
+                if (xmn == 0.0) continue;                  // g / 0: not finite
+                sure = xmn >= R3_TINY && rmx < R3_BIG * xmn;
+                amx = rmx; fmx = rmx / xmn; bmx = 1.0 / xmn;
+            }
+            const double varn = S2[e] - S1[e] * (S1[e] / nn);
+            const double kappa = varn > 0.0 ? S2[e] / varn : INFINITY;
+            const bool lp_ok = amx < LP_BIG && fmx < LP_BIG && bmx < LP_BIG && S2[e] > LP_SMALL * LP_SMALL;
+            if (!sure || !lp_ok || !(kappa <= R3_KAPPA_MAX)) {
+                const unsigned long long slot = r3_slot(g.fix_cnt);
+                if ((int64_t)slot < g.fix_cap) g.fix_ids[slot] = id;
+                continue;
+            }
+            const double isd = 1.0 / sqrt(varn);
+            const bool precise = kappa <= LP_KAPPA;
+            const double ub = a.delta * sqrt(kappa) + 4.0 * nn * 1.1102230246251565e-16 * kappa;
+            cnt++;
+            if (g.mode == DISCOVER_SCORE_MAX) {
+                double best = 0.0;
+#pragma unroll
+                for (int t = 0; t < TP; t++)
+                    if (t < g.T) best = fmax(best, fabs(((double)pa[u][t][e] - S1[e] * (g.ysum[t] / nn)) * isd));
+                g.scores[id] = precise ? best : -(best + ub);
+            } else {
+#pragma unroll
+                for (int t = 0; t < TP; t++)
+                    if (t < g.T) {
+                        const double r = fabs(((double)pa[u][t][e] - S1[e] * (g.ysum[t] / nn)) * isd);
+                        g.scores[(int64_t)t * g.N + id] = precise ? r : -(r + ub);
+                    }
+            }
         }
     }
     for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor((int)cnt, o, 64);
     if (lane == 0 && cnt) atomicAdd(g.nscored, (unsigned long long)cnt);
+}
+
+template <int TP, int GT>
+void launch_lp(R3lpArgs l, int nct, int64_t n_grec, hipStream_t st) {
+    l.m.n_gblk = (int)((n_grec / 16 + 4 * GT - 1) / (4 * GT));
+    const int64_t blocks = (int64_t)l.m.n_gblk * nct;
+    DSC_REQUIRE(blocks < ((int64_t)1 << 31), "rung-3 grid too large");
+    k_r3_lp<TP, GT><<<(unsigned)blocks, 256, 0, st>>>(l);
 }
 
 template <class T>
@@ -836,17 +886,14 @@ void launch_r3(discover_ctx* ctx, const R3Launch& a, hipStream_t st) {
         m.valid = a.valid; m.mat_raw = a.mat_raw; m.r2v = a.r2v; m.ysum = a.ysum; m.sd = a.sd;
         m.N = a.N; m.scores = a.scores; m.nscored = a.nscored; m.fix_ids = a.fix_ids;
         m.fix_cnt = a.fix_cnt; m.fix_cap = a.fix_cap;
-        m.n_gblk = (int)((P.n_grec / 16 + 3) / 4);
         l.b64 = b64; l.blp = blp; l.NC = NC; l.delta = a.delta;
-        const int64_t blocks = (int64_t)m.n_gblk * P.n_ctiles;
-        DSC_REQUIRE(blocks < ((int64_t)1 << 31), "rung-3 grid too large");
         KTimer kt(ctx, st, "screen_r3");
         switch (a.TP) {
-        case 1: k_r3_lp<1><<<(unsigned)blocks, 256, 0, st>>>(l); break;
-        case 2: k_r3_lp<2><<<(unsigned)blocks, 256, 0, st>>>(l); break;
-        case 4: k_r3_lp<4><<<(unsigned)blocks, 256, 0, st>>>(l); break;
-        case 8: k_r3_lp<8><<<(unsigned)blocks, 256, 0, st>>>(l); break;
-        default: k_r3_lp<16><<<(unsigned)blocks, 256, 0, st>>>(l); break;
+        case 1: launch_lp<1, 1>(l, P.n_ctiles, P.n_grec, st); break;
+        case 2: launch_lp<2, 1>(l, P.n_ctiles, P.n_grec, st); break;
+        case 4: launch_lp<4, 1>(l, P.n_ctiles, P.n_grec, st); break;
+        case 8: launch_lp<8, 1>(l, P.n_ctiles, P.n_grec, st); break;
+        default: launch_lp<16, 1>(l, P.n_ctiles, P.n_grec, st); break;
         }
         check_launch("k_r3_lp");
     } else if (P.n_grec && P.n_ctiles) {
