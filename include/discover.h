@@ -19,9 +19,35 @@
  *     caller owns every input and output buffer; the library never frees
  *     caller memory.  The context owns only its internal workspace.
  *   - `stream` is a hipStream_t (NULL = the default stream).  Work is
- *     enqueued on it; every call returns after its results are complete
- *     (calls synchronise the stream, because pool sizes are data
- *     dependent).
+ *     enqueued on it.  Screening and L0 pool sizes are data dependent, so
+ *     how a call waits depends on where its stats go:
+ *       * out_stats NULL or host memory: the call waits for the stream,
+ *         regrows any pool that overflowed and runs again, and returns with
+ *         its results complete;
+ *       * out_stats device memory: the call does not wait.  It runs once at
+ *         the sizes that an earlier call of the same shape (parameters,
+ *         sizes, units; not the data) settled on, and each problem's
+ *         stats.status reports, on the device, DISCOVER_OK or why the
+ *         outputs are not valid (E_CAPACITY: a pool was too small for this
+ *         data, so run the call once with host stats to grow it;
+ *         E_NUMERIC).  The first call of a shape sizes its pools as a host
+ *         call does, waiting once; discover_reserve does that ahead of time.
+ *     discover_omp never waits.  The outputs are valid once the stream has
+ *     completed the work.  A context's calls must be ordered (one stream, or
+ *     streams the caller orders): they share the context's workspace.
+ *   - Graph capture: a screening, L0 or OMP call made on a stream that the
+ *     caller is capturing (hipStreamBeginCapture, torch.cuda.graph) is
+ *     recorded into the caller's graph.  It must pass out_stats in device
+ *     memory, and a call of the same shape must have run outside capture
+ *     first (or discover_reserve), else it returns E_CAPACITY.  The library
+ *     may allocate workspace and upload argument tables through a private
+ *     stream while the capture runs: capture in relaxed mode
+ *     (hipStreamCaptureModeRelaxed; torch: capture_error_mode="relaxed").
+ *     Every replay recomputes the outputs and stats from the inputs'
+ *     current contents.  Workspace that a captured graph references is
+ *     never freed while the context lives: a later call that would have to
+ *     grow it returns E_CAPACITY (reserve first, or use a separate
+ *     context).  Destroy the graph before the context.
  *   - Errors: every argument is validated before any launch; on error the
  *     call returns a negative discover_status, writes no output, and
  *     discover_last_error() describes the failure.  No C++ exception or
@@ -142,7 +168,8 @@ typedef struct {
     int32_t tile_j;           /* FP64 dense pair kernel: operand features per wave,
                                  chosen by timing 1/2/4 on the first call for a
                                  search space (0 when that kernel did not run) */
-    int32_t reserved;
+    int32_t status;           /* DISCOVER_OK, or (device stats) E_CAPACITY / E_NUMERIC:
+                                 this problem's outputs are not valid */
 } discover_screen_stats;
 
 /* Enumerate the candidates of P_R (rungs 0..R), drop those failing the unit
@@ -166,9 +193,11 @@ typedef struct {
  *   out_values device double [n_problems][T'][k][ldv] values of the selected
  *              features, or NULL
  *   ldv        >= max n when out_values is not NULL
- *   out_stats  host, n_problems entries, or NULL
+ *   out_stats  host or device, n_problems entries, or NULL (see the conventions:
+ *              device stats make the call asynchronous and capturable)
  * Errors: E_ARG, E_NUMERIC (constant target), E_NOMEM, E_HIP,
- * E_UNSUPPORTED (rung 3 without an operator-limited partner pool). */
+ * E_UNSUPPORTED (rung 3 without an operator-limited partner pool),
+ * E_CAPACITY (captured before a call of this shape ran). */
 discover_status discover_generate_screen(discover_ctx* ctx, const discover_problem* probs,
                                          int32_t n_problems, const discover_screen_params* prm,
                                          int64_t* out_ids, double* out_scores,
@@ -189,6 +218,9 @@ typedef struct {
     int64_t n_subsets;        /* C(S, D) */
     int64_t n_band;           /* subsets refitted by Householder QR */
     int64_t n_singular;       /* (informational) 0 when not counted */
+    int32_t status;           /* DISCOVER_OK, or (device stats) E_CAPACITY (the band
+                                 overflowed) / E_NUMERIC (no non-singular subset) */
+    int32_t reserved;
 } discover_l0_stats;
 
 /* Exhaustive L0 (Eq. (1), Core Optimization Objective) with an intercept:
@@ -209,7 +241,9 @@ typedef struct {
  *   out_coef     device double [n_problems][m][D+1], intercept first, then the rows in
  *                ascending order
  *   out_resid    device double [n_problems][m][ldr] residuals y - prediction, or NULL
- *   out_stats    host [n_problems] or NULL
+ *   out_stats    host or device [n_problems], or NULL (device: asynchronous, capturable;
+ *                a call with no earlier call of its shape starts from the default
+ *                band size)
  * Errors: E_ARG, E_NUMERIC (constant y, or no non-singular subset), E_NOMEM, E_HIP. */
 discover_status discover_l0_fit(discover_ctx* ctx, const discover_l0_problem* probs,
                                 int32_t n_problems, int32_t D, int32_t m,
@@ -232,6 +266,8 @@ discover_status discover_l0_fit(discover_ctx* ctx, const discover_l0_problem* pr
  *                in order of addition
  *   out_rmse     device double [n_problems]
  *   out_resid    device double [n_problems][ldr] or NULL
+ * The call does not wait for the stream (the method has no data-dependent
+ * sizes here) and can be captured.
  * Errors: E_ARG (D_max > S or D_max > DISCOVER_MAX_D), E_NOMEM, E_HIP. */
 discover_status discover_omp(discover_ctx* ctx, const discover_l0_problem* probs,
                              int32_t n_problems, int32_t D_max,
@@ -277,6 +313,21 @@ discover_status discover_sisso_batch(discover_ctx* ctx, const discover_problem* 
                                      double* out_rmse, double* out_coef, int32_t omp_D,
                                      int32_t* out_omp_active, double* out_omp_coef,
                                      double* out_omp_rmse, int32_t* out_replayed, void* stream);
+
+/* Sizes the context's workspace for later calls that must not wait or
+ * allocate (device stats, graph capture): runs discover_generate_screen on
+ * these problems and parameters with host stats (settling plans, tile
+ * choices and selection pool sizes for this shape and data), then, for
+ * every D in 1..D_max, discover_l0_fit with m models over stand-in
+ * subspaces of D * k * T' rows (T' = T per target, 1 in MAX mode) of each
+ * problem's n, and discover_omp up to DISCOVER_MAX_D rows over the last of
+ * them.  Call it once per call shape to be captured.  Waits for the stream.
+ *   D_max  0..3 (0: screening only);  m  1..64 when D_max > 0
+ * Errors: as discover_generate_screen and discover_l0_fit; E_ARG while the
+ * stream is capturing. */
+discover_status discover_reserve(discover_ctx* ctx, const discover_problem* probs, int32_t n_problems,
+                                 const discover_screen_params* prm, int32_t D_max, int32_t m,
+                                 void* stream);
 
 /* Initial capacity (entries per problem, >= 1) of the screening's exact
  * fix-up lists: candidates whose one-pass moments cannot be trusted (a

@@ -45,7 +45,7 @@ class ScreenStats(C.Structure):
     _fields_ = [("n_raw", C.c_int64), ("n_unit_valid", C.c_int64), ("n_scored", C.c_int64),
                 ("pool_size", C.c_int64), ("pool_rounds", C.c_int64), ("n_merged", C.c_int64),
                 ("n_selected", C.c_int64), ("max_lowprec_err", C.c_double),
-                ("guard_band", C.c_double), ("tile_j", C.c_int32), ("reserved", C.c_int32)]
+                ("guard_band", C.c_double), ("tile_j", C.c_int32), ("status", C.c_int32)]
 
     def asdict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -57,7 +57,8 @@ class L0Problem(C.Structure):
 
 
 class L0Stats(C.Structure):
-    _fields_ = [("n_subsets", C.c_int64), ("n_band", C.c_int64), ("n_singular", C.c_int64)]
+    _fields_ = [("n_subsets", C.c_int64), ("n_band", C.c_int64), ("n_singular", C.c_int64),
+                ("status", C.c_int32), ("reserved", C.c_int32)]
 
     def asdict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -67,7 +68,8 @@ class L0Stats(C.Structure):
 SYMBOLS = ("discover_create", "discover_destroy", "discover_last_error",
            "discover_generate_screen", "discover_l0_fit", "discover_omp", "discover_count",
            "discover_decode", "discover_set_timing", "discover_timing", "discover_reset_timing",
-           "discover_sisso_batch", "discover_set_graph_timing", "discover_set_fixup_capacity")
+           "discover_sisso_batch", "discover_set_graph_timing", "discover_set_fixup_capacity",
+           "discover_reserve")
 
 _lib = None
 
@@ -84,11 +86,13 @@ def lib():
         L.discover_destroy.argtypes = [P]
         L.discover_destroy.restype = None
         L.discover_last_error.restype = C.c_char_p
+        # stats: host structures (byref / arrays) or a device address
         L.discover_generate_screen.argtypes = [P, C.POINTER(Problem), C.c_int32,
-                                               C.POINTER(ScreenParams), P, P, P, C.c_int64,
-                                               C.POINTER(ScreenStats), P]
+                                               C.POINTER(ScreenParams), P, P, P, C.c_int64, P, P]
         L.discover_l0_fit.argtypes = [P, C.POINTER(L0Problem), C.c_int32, C.c_int32, C.c_int32,
-                                      P, P, P, P, C.c_int64, C.POINTER(L0Stats), P]
+                                      P, P, P, P, C.c_int64, P, P]
+        L.discover_reserve.argtypes = [P, C.POINTER(Problem), C.c_int32, C.POINTER(ScreenParams),
+                                       C.c_int32, C.c_int32, P]
         L.discover_omp.argtypes = [P, C.POINTER(L0Problem), C.c_int32, C.c_int32, P, C.c_int32,
                                    P, P, P, P, C.c_int64, P]
         L.discover_count.argtypes = [C.c_int32, C.POINTER(ScreenParams)]
@@ -144,6 +148,16 @@ def decode(p, prm, cid):
     return buf.value.decode()
 
 
+def decode_stats(t, cls):
+    """Stats written to device memory (the byte tensor of a call with
+    device_stats; cls = ScreenStats or L0Stats): a list of dicts, one per
+    problem."""
+    raw = bytes(t.cpu().numpy().tobytes())
+    nb = len(raw) // C.sizeof(cls)
+    arr = (cls * nb).from_buffer_copy(raw)
+    return [arr[b].asdict() for b in range(nb)]
+
+
 def _stream_handle(torch, device):
     return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
@@ -193,65 +207,19 @@ class Context:
         return int(n.value), float(ms.value)
 
     # ------------------------------------------------------------ calls
-    def generate_screen(self, X, Y, prm, units=None, exclude=None, values=True):
-        """X [p][n], Y [T][n] float64 CUDA tensors; units [p][B] int32 host
-        array or None; exclude int64 CUDA tensor of IDs or None.
-        Returns (ids [T'][k], scores [T'][k], values [T'][k][n] or None, stats)."""
-        torch = self.torch
-        import numpy as np
-        X = X.contiguous()
-        Y = Y.contiguous()
-        p, n = X.shape
-        T = Y.shape[0]
-        Tl = 1 if prm.score_mode == SCORE_MAX else T
-        dev = X.device
-        ids = torch.empty((Tl, prm.k), dtype=torch.int64, device=dev)
-        sc = torch.empty((Tl, prm.k), dtype=torch.float64, device=dev)
-        vals = torch.empty((Tl, prm.k, n), dtype=torch.float64, device=dev) if values else None
-        pb = Problem()
-        pb.n, pb.p, pb.T = n, p, T
-        u = None
-        if units is not None:
-            u = np.ascontiguousarray(units, dtype=np.int32)
-            pb.B = u.shape[1]
-            pb.units = u.ctypes.data
-        else:
-            pb.B = 0
-        pb.X, pb.ldx = X.data_ptr(), n
-        pb.Y, pb.ldy = Y.data_ptr(), n
-        if exclude is not None and exclude.numel():
-            exclude = exclude.contiguous()
-            pb.exclude, pb.n_exclude = exclude.data_ptr(), exclude.numel()
-        st = ScreenStats()
-        _check(lib().discover_generate_screen(
-            self.h, C.byref(pb), 1, C.byref(prm), ids.data_ptr(), sc.data_ptr(),
-            vals.data_ptr() if vals is not None else None, n, C.byref(st),
-            _stream_handle(torch, dev)))
-        return ids, sc, vals, st.asdict()
-
-    def generate_screen_batch(self, Xs, Ys, prm, units=None, excludes=None, values=True):
-        """One call over many datasets: Xs[b] [p_b][n_b], Ys[b] [T_b][n_b]
-        float64 CUDA tensors; units[b] host [p_b][B] int32 or None;
-        excludes[b] int64 CUDA tensor or None.  Returns per-dataset lists
-        (ids [T'_b][k], scores, values [T'_b][k][n_max] or None, stats)."""
-        torch = self.torch
+    def _problems(self, Xs, Ys, units, excludes):
+        """Problem structures of many datasets (and the objects they point to)."""
         import numpy as np
         nb = len(Xs)
-        Xs = [x.contiguous() for x in Xs]
-        Ys = [y.contiguous() for y in Ys]
-        dev = Xs[0].device
-        tl = [1 if prm.score_mode == SCORE_MAX else y.shape[0] for y in Ys]
-        rows = sum(tl)
-        nmax = max(x.shape[1] for x in Xs)
-        ids = torch.empty((rows, prm.k), dtype=torch.int64, device=dev)
-        sc = torch.empty((rows, prm.k), dtype=torch.float64, device=dev)
-        vals = torch.empty((rows, prm.k, nmax), dtype=torch.float64, device=dev) if values else None
         pbs = (Problem * nb)()
         keep = []
         for b in range(nb):
             pb = pbs[b]
-            p_, n_ = Xs[b].shape
-            pb.n, pb.p, pb.T = n_, p_, Ys[b].shape[0]
+            X = Xs[b].contiguous()
+            Y = Ys[b].contiguous()
+            keep += [X, Y]
+            p_, n_ = X.shape
+            pb.n, pb.p, pb.T = n_, p_, Y.shape[0]
             u = units[b] if units is not None else None
             if u is not None:
                 u = np.ascontiguousarray(u, dtype=np.int32)
@@ -259,29 +227,75 @@ class Context:
                 pb.B, pb.units = u.shape[1], u.ctypes.data
             else:
                 pb.B = 0
-            pb.X, pb.ldx = Xs[b].data_ptr(), n_
-            pb.Y, pb.ldy = Ys[b].data_ptr(), n_
+            pb.X, pb.ldx = X.data_ptr(), n_
+            pb.Y, pb.ldy = Y.data_ptr(), n_
             e = excludes[b] if excludes is not None else None
             if e is not None and e.numel():
                 e = e.contiguous()
                 keep.append(e)
                 pb.exclude, pb.n_exclude = e.data_ptr(), e.numel()
-        st = (ScreenStats * nb)()
+        return pbs, keep
+
+    def _stats(self, cls, nb, device_stats, dev):
+        """Host stats structures, or a device byte tensor for them."""
+        if device_stats:
+            t = self.torch.zeros(nb * C.sizeof(cls), dtype=self.torch.uint8, device=dev)
+            return t, t.data_ptr()
+        st = (cls * nb)()
+        return st, st
+
+    def generate_screen(self, X, Y, prm, units=None, exclude=None, values=True, device_stats=False):
+        """X [p][n], Y [T][n] float64 CUDA tensors; units [p][B] int32 host
+        array or None; exclude int64 CUDA tensor of IDs or None.
+        Returns (ids [T'][k], scores [T'][k], values [T'][k][n] or None, stats);
+        with device_stats the call does not wait for the stream and stats is
+        a device byte tensor (decode_stats)."""
+        ((ids, sc, vals, st),) = self.generate_screen_batch(
+            [X], [Y], prm, units=None if units is None else [units],
+            excludes=None if exclude is None else [exclude], values=values, device_stats=device_stats)
+        return ids, sc, vals, st
+
+    def generate_screen_batch(self, Xs, Ys, prm, units=None, excludes=None, values=True,
+                              device_stats=False):
+        """One call over many datasets: Xs[b] [p_b][n_b], Ys[b] [T_b][n_b]
+        float64 CUDA tensors; units[b] host [p_b][B] int32 or None;
+        excludes[b] int64 CUDA tensor or None.  Returns per-dataset lists
+        (ids [T'_b][k], scores, values [T'_b][k][n_max] or None, stats); with
+        device_stats every stats entry is the call's device byte tensor."""
+        torch = self.torch
+        nb = len(Xs)
+        dev = Xs[0].device
+        tl = [1 if prm.score_mode == SCORE_MAX else y.shape[0] for y in Ys]
+        rows = sum(tl)
+        nmax = max(x.shape[1] for x in Xs)
+        ids = torch.empty((rows, prm.k), dtype=torch.int64, device=dev)
+        sc = torch.empty((rows, prm.k), dtype=torch.float64, device=dev)
+        vals = torch.empty((rows, prm.k, nmax), dtype=torch.float64, device=dev) if values else None
+        pbs, keep = self._problems(Xs, Ys, units, excludes)
+        st, sp = self._stats(ScreenStats, nb, device_stats, dev)
         _check(lib().discover_generate_screen(
             self.h, pbs, nb, C.byref(prm), ids.data_ptr(), sc.data_ptr(),
-            vals.data_ptr() if vals is not None else None, nmax, st, _stream_handle(torch, dev)))
+            vals.data_ptr() if vals is not None else None, nmax, sp, _stream_handle(torch, dev)))
         out, r = [], 0
         for b in range(nb):
             out.append((ids[r:r + tl[b]], sc[r:r + tl[b]],
                         vals[r:r + tl[b], :, :Xs[b].shape[1]] if vals is not None else None,
-                        st[b].asdict()))
+                        st if device_stats else st[b].asdict()))
             r += tl[b]
         return out
 
-    def l0_fit_batch(self, Fs, idss, ys, D, m=1, resid=True):
+    def reserve(self, Xs, Ys, prm, D_max=0, m=1, units=None, excludes=None):
+        """Size the workspace for later asynchronous or captured calls of this
+        screening shape, and L0 / OMP up to D_max dimensions (waits)."""
+        pbs, keep = self._problems(Xs, Ys, units, excludes)
+        _check(lib().discover_reserve(self.h, pbs, len(Xs), C.byref(prm), D_max, m,
+                                      _stream_handle(self.torch, Xs[0].device)))
+
+    def l0_fit_batch(self, Fs, idss, ys, D, m=1, resid=True, device_stats=False):
         """Exhaustive L0 of many subspaces in one call: Fs[b] [S_b][n_b],
         idss[b] [S_b] int64, ys[b] [n_b] (CUDA).  Returns per-dataset lists
-        (subsets [m][D], rmse [m], coef [m][D+1], resid [m][n_b] or None, stats)."""
+        (subsets [m][D], rmse [m], coef [m][D+1], resid [m][n_b] or None, stats);
+        with device_stats every stats entry is the call's device byte tensor."""
         torch = self.torch
         nb = len(Fs)
         Fs = [f.contiguous() for f in Fs]
@@ -298,36 +312,20 @@ class Context:
             S, n = Fs[b].shape
             pbs[b].n, pbs[b].S, pbs[b].F, pbs[b].ldf = n, S, Fs[b].data_ptr(), n
             pbs[b].ids, pbs[b].y = idss[b].data_ptr(), ys[b].data_ptr()
-        st = (L0Stats * nb)()
+        st, sp = self._stats(L0Stats, nb, device_stats, dev)
         _check(lib().discover_l0_fit(self.h, pbs, nb, D, m, sub.data_ptr(), rmse.data_ptr(),
                                      coef.data_ptr(), res.data_ptr() if res is not None else None,
-                                     nmax, st, _stream_handle(torch, dev)))
+                                     nmax, sp, _stream_handle(torch, dev)))
         return [(sub[b], rmse[b], coef[b],
-                 res[b, :, :Fs[b].shape[1]] if res is not None else None, st[b].asdict())
+                 res[b, :, :Fs[b].shape[1]] if res is not None else None,
+                 st if device_stats else st[b].asdict())
                 for b in range(nb)]
 
-    def l0_fit(self, F, ids, y, D, m=1, resid=True):
+    def l0_fit(self, F, ids, y, D, m=1, resid=True, device_stats=False):
         """F [S][n] float64, ids [S] int64, y [n] float64 (CUDA).  Returns
         (subsets [m][D] rows, rmse [m], coef [m][D+1], resid [m][n], stats)."""
-        torch = self.torch
-        F = F.contiguous()
-        S, n = F.shape
-        dev = F.device
-        sub = torch.empty((m, D), dtype=torch.int32, device=dev)
-        rmse = torch.empty(m, dtype=torch.float64, device=dev)
-        coef = torch.empty((m, D + 1), dtype=torch.float64, device=dev)
-        res = torch.empty((m, n), dtype=torch.float64, device=dev) if resid else None
-        pb = L0Problem()
-        pb.n, pb.S, pb.F, pb.ldf = n, S, F.data_ptr(), n
-        ids = ids.contiguous()
-        y = y.contiguous()
-        pb.ids, pb.y = ids.data_ptr(), y.data_ptr()
-        st = L0Stats()
-        _check(lib().discover_l0_fit(self.h, C.byref(pb), 1, D, m, sub.data_ptr(),
-                                     rmse.data_ptr(), coef.data_ptr(),
-                                     res.data_ptr() if res is not None else None, n,
-                                     C.byref(st), _stream_handle(torch, dev)))
-        return sub, rmse, coef, res, st.asdict()
+        ((sub, rmse, coef, res, st),) = self.l0_fit_batch([F], [ids], [y], D, m, resid, device_stats)
+        return sub, rmse, coef, res, st
 
     def omp(self, F, ids, y, D_max, init=None):
         """OMP over the rows of F from the warm start ``init`` (int32 CUDA

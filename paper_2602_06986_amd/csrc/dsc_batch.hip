@@ -23,14 +23,11 @@ __global__ __launch_bounds__(256) void k_verdict(ctab<ListCheck> L, int nl, ctab
     if (i < nl) {
         const ListCheck& c = tab(L, i);
         DSC_GLOBAL(c.res); DSC_GLOBAL(c.ctr);
-        const int64_t* r = c.res;
-        bad = r[4] > c.cap || (c.dedup && r[3] > c.fcap) || !(r[1] || c.K >= c.N) ||
-              (c.ctr[0] & 0xFFFFFFFFull) != 0 ||
-              (int64_t)c.ctr[1] > c.fix_cap || (int64_t)c.ctr[3] > c.fix_cap;
+        bad = list_status(c, c.res, c.ctr) != DISCOVER_OK;
     } else if (i < nl + nbc) {
         const BandCheck& c = tab(B, i - nl);
         DSC_GLOBAL(c.cnt);
-        bad = (int64_t)c.cnt[0] > c.cap || (int64_t)c.cnt[1] > c.cap || c.cnt[0] == 0;
+        bad = band_status(c, c.cnt) != DISCOVER_OK;
     }
     if (bad) *(volatile int*)out = 1;
 }
@@ -215,6 +212,8 @@ extern "C" discover_status discover_sisso_batch(discover_ctx* ctx, const discove
         }
         DSC_HIP(hipSetDevice(ctx->device));
         hipStream_t caller = (hipStream_t)stream;
+        DSC_REQUIRE(!stream_capturing(caller), "discover_sisso_batch captures and replays graphs of its "
+                                               "own and cannot itself be captured");
         if (out_replayed) *out_replayed = 0;
         SissoCall c{probs, n_problems, *prm, D, m, prm->k, (int)cdiv(nmax, 64) * 64,
                     out_ids, out_scores, out_subsets, out_rmse, out_coef, omp_D, out_omp_active,
@@ -307,5 +306,121 @@ extern "C" discover_status discover_sisso_batch(discover_ctx* ctx, const discove
         G->graph = graph;
         G->exec = exec;
         G->generation = ctx->generation;
+    });
+}
+
+namespace dsc {
+
+// Values of the stand-in subspaces that size the L0 workspace: uniform on
+// [0.5, 2) from a counter hash (splitmix64), so that every subset is
+// non-singular and the band keeps its default size.
+__global__ __launch_bounds__(256) void k_reserve_fill(double* __restrict__ v, int64_t count, uint64_t seed) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < count; i += (int64_t)gridDim.x * 256) {
+        uint64_t z = seed + (uint64_t)i * 0x9E3779B97F4A7C15ull;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        v[i] = 0.5 + 1.5 * (double)(z >> 11) * 0x1.0p-53;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_reserve_iota(int64_t* __restrict__ v, const int64_t* __restrict__ start,
+                                                      const int32_t* __restrict__ len, int nb) {
+    const int b = blockIdx.y;
+    if (b >= nb) return;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < len[b]; i += (int64_t)gridDim.x * 256)
+        v[start[b] + i] = i;
+}
+
+}  // namespace dsc
+
+static void rethrow(discover_status s) {
+    if (s != DISCOVER_OK) throw dsc::Error{s};
+}
+
+extern "C" discover_status discover_reserve(discover_ctx* ctx, const discover_problem* probs,
+                                            int32_t n_problems, const discover_screen_params* prm,
+                                            int32_t D_max, int32_t m, void* stream) {
+    using namespace dsc;
+    return guarded([&] {
+        DSC_REQUIRE(ctx && probs && prm && n_problems >= 1, "ctx/probs/prm");
+        DSC_REQUIRE(n_problems <= 65535, "n_problems = %d > 65535", n_problems);
+        DSC_REQUIRE(D_max >= 0 && D_max <= 3, "D_max = %d outside 0..3", D_max);
+        DSC_REQUIRE(D_max == 0 || (m >= 1 && m <= 64), "m = %d outside 1..64", m);
+        DSC_REQUIRE(prm->k >= 1, "k must be >= 1");
+        DSC_HIP(hipSetDevice(ctx->device));
+        const hipStream_t st = (hipStream_t)stream;
+        DSC_REQUIRE(!stream_capturing(st), "discover_reserve cannot run inside a graph capture");
+        // 1. the screen itself, eagerly: plans, tile choices, selection sizes
+        int64_t rows = 0;
+        int nmax = 0;
+        std::vector<int> tl(n_problems);
+        for (int b = 0; b < n_problems; b++) {
+            tl[b] = prm->score_mode == DISCOVER_SCORE_MAX ? 1 : probs[b].T;
+            rows += tl[b];
+            nmax = std::max(nmax, probs[b].n);
+        }
+        DSC_REQUIRE(nmax >= 1, "n");
+        int64_t* ids = ctx->buf<int64_t>("rsv_ids", (size_t)rows * prm->k);
+        double* sc = ctx->buf<double>("rsv_sc", (size_t)rows * prm->k);
+        double* vals = ctx->buf<double>("rsv_vals", (size_t)rows * prm->k * nmax);
+        std::vector<discover_screen_stats> ss(n_problems);
+        rethrow(discover_generate_screen(ctx, probs, n_problems, prm, ids, sc, vals, nmax, ss.data(), stream));
+        // 2. L0 of every dimension up to D_max over D * k * T' rows, then OMP,
+        // on stand-in subspaces of the same sizes
+        for (int D = 1; D <= D_max; D++) {
+            std::vector<discover_l0_problem> lp;
+            std::vector<int64_t> fo, io;
+            int64_t ftot = 0, itot = 0, ytot = 0;
+            std::vector<int64_t> yo;
+            for (int b = 0; b < n_problems; b++) {
+                const int64_t S = std::min<int64_t>(65535, (int64_t)D * prm->k * tl[b]);
+                if (S < D || probs[b].n < D + 2) continue;
+                discover_l0_problem q{};
+                q.n = probs[b].n;
+                q.S = (int32_t)S;
+                q.ldf = q.n;
+                lp.push_back(q);
+                fo.push_back(ftot); io.push_back(itot); yo.push_back(ytot);
+                ftot += S * q.n; itot += S; ytot += q.n;
+            }
+            if (lp.empty()) continue;
+            const int nl = (int)lp.size();
+            double* F = ctx->buf<double>("rsv_F", (size_t)ftot);
+            double* y = ctx->buf<double>("rsv_y", (size_t)ytot);
+            int64_t* rid = ctx->buf<int64_t>("rsv_rid", (size_t)itot);
+            k_reserve_fill<<<(unsigned)std::min<int64_t>(4096, cdiv(ftot, 256)), 256, 0, st>>>(F, ftot, 0x5EEDull + D);
+            k_reserve_fill<<<(unsigned)std::min<int64_t>(4096, cdiv(ytot, 256)), 256, 0, st>>>(y, ytot, 0xF00Dull + D);
+            std::vector<int32_t> len(nl);
+            int32_t lmax = 1;
+            for (int q = 0; q < nl; q++) { len[q] = lp[q].S; lmax = std::max(lmax, len[q]); }
+            const int64_t* dio = ctx->upload("rsv_io", io, st);
+            const int32_t* dlen = ctx->upload("rsv_len", len, st);
+            k_reserve_iota<<<dim3((unsigned)cdiv(lmax, 256), nl), 256, 0, st>>>(rid, dio, dlen, nl);
+            check_launch("k_reserve");
+            for (int q = 0; q < nl; q++) {
+                lp[q].F = F + fo[q];
+                lp[q].y = y + yo[q];
+                lp[q].ids = rid + io[q];
+            }
+            int32_t* sub = ctx->buf<int32_t>("rsv_sub", (size_t)nl * m * D);
+            double* rmse = ctx->buf<double>("rsv_rmse", (size_t)nl * m);
+            double* coef = ctx->buf<double>("rsv_coef", (size_t)nl * m * (D + 1));
+            double* res = ctx->buf<double>("rsv_res", (size_t)nl * m * nmax);
+            std::vector<discover_l0_stats> ls(nl);
+            rethrow(discover_l0_fit(ctx, lp.data(), nl, D, m, sub, rmse, coef, res, nmax, ls.data(), stream));
+            if (D == D_max) {
+                int Do = DISCOVER_MAX_D;
+                for (const auto& q : lp) Do = std::min({Do, q.S, q.n - 2});
+                if (Do >= 1) {
+                    int32_t* act = ctx->buf<int32_t>("rsv_oact", (size_t)nl * Do);
+                    double* oc = ctx->buf<double>("rsv_ocoef", (size_t)nl * (Do + 1));
+                    double* orm = ctx->buf<double>("rsv_ormse", (size_t)nl);
+                    double* ores = ctx->buf<double>("rsv_ores", (size_t)nl * nmax);
+                    rethrow(discover_omp(ctx, lp.data(), nl, Do, nullptr, 0, act, oc, orm, ores, nmax, stream));
+                }
+            }
+        }
+        DSC_HIP(hipStreamSynchronize(st));
     });
 }

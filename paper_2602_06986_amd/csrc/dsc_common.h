@@ -75,6 +75,7 @@ struct discover_ctx {
     struct Buf {
         void* p = nullptr;
         size_t cap = 0;
+        bool bound = false;    // referenced by a graph a caller captured: never freed
     };
     std::map<std::string, Buf> bufs;
     // small pinned host buffers (hipHostMalloc) that kernels write and the
@@ -111,6 +112,18 @@ struct discover_ctx {
     // allocate, synchronise or copy from the host: buffers must already be
     // large enough and argument tables already uploaded.
     bool capturing = false;
+    // The capture in progress is the caller's (a public call made on a
+    // stream the caller is capturing): buffers it touches become bound, and
+    // new ones may be allocated, which a capture in relaxed mode permits.
+    bool caller_capture = false;
+    // Set once a caller has captured a call: search-space plans are then
+    // never evicted (their device tables may be referenced by that graph).
+    bool frozen = false;
+    int64_t capture_seq = 0;
+    // The call reports its outcome in device memory and must not wait for
+    // the stream: one selection round at the remembered sizes, checked on
+    // the device.
+    bool nosync = false;
     // Suffix of argument-table and result-buffer names, so that the calls of
     // one captured sequence keep tables of their own.
     std::string tag;
@@ -137,9 +150,15 @@ struct discover_ctx {
         Buf& b = bufs[name];
         if (bytes == 0) bytes = 256;
         if (b.cap < bytes) {
-            if (capturing)
-                DSC_FAIL(DISCOVER_E_CAPACITY, "buffer %s would grow during graph capture",
+            if (b.bound)
+                DSC_FAIL(DISCOVER_E_CAPACITY,
+                         "buffer %s is referenced by a graph captured from this context and cannot "
+                         "grow (reserve larger sizes before capturing, or use another context)",
                          name.c_str());
+            if (capturing && !(caller_capture && !b.p))
+                DSC_FAIL(DISCOVER_E_CAPACITY,
+                         "buffer %s would grow during graph capture (run the call, or "
+                         "discover_reserve, outside capture first)", name.c_str());
             if (b.p) {
                 hipError_t e = hipFree(b.p);
                 (void)e;
@@ -151,11 +170,18 @@ struct discover_ctx {
             want = (want + 4095) & ~size_t(4095);
             if (hipMalloc(&b.p, want) != hipSuccess) {
                 b.p = nullptr;
+                (void)hipGetLastError();
+                if (capturing)
+                    DSC_FAIL(DISCOVER_E_CAPACITY,
+                             "allocation of %zu bytes (%s) during graph capture failed: capture in "
+                             "relaxed mode, or size the workspace (discover_reserve) first",
+                             want, name.c_str());
                 DSC_FAIL(DISCOVER_E_NOMEM, "device allocation of %zu bytes (%s) failed", want,
                          name.c_str());
             }
             b.cap = want;
         }
+        if (caller_capture) b.bound = true;
         return b.p;
     }
     template <class T>
@@ -196,6 +222,14 @@ struct discover_ctx {
     }
     std::map<std::string, void*> shadow_ptr;
 
+    // Drops the cached search-space plans when there are too many, unless a
+    // captured graph may reference their tables.
+    void evict_plans(size_t limit) {
+        if (frozen || plans.size() < limit) return;
+        plans.clear();
+        generation++;
+    }
+
     hipEvent_t event() {
         if (!free_events.empty()) {
             hipEvent_t e = free_events.back();
@@ -206,11 +240,11 @@ struct discover_ctx {
         DSC_HIP(hipEventCreate(&e));
         return e;
     }
-    // Accumulate the pending kernel times (the stream must be synchronised).
+    // Accumulate the pending kernel times (waits for the kernels still running).
     void resolve_timing() {
         for (auto& p : pending) {
             float ms = 0.f;
-            if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
                 auto& t = times[p.name];
                 t.first += 1;
                 t.second += ms;
@@ -253,7 +287,7 @@ struct KTimer {
             a = c->event();
             b = c->event();
             DSC_HIP(hipEventRecord(a, s));
-        } else if (c->capturing && c->graph_timed.count(name)) {
+        } else if (c->capturing && !c->caller_capture && c->graph_timed.count(name)) {
             // event-record nodes of the graph: the pair belongs to the graph
             graph = true;
             DSC_HIP(hipEventCreate(&a));

@@ -26,7 +26,20 @@ struct ListCheck {
     const unsigned long long* ctr;
     int dedup;
     int64_t fix_cap;          // entries of the problem's two fix-up lists (ctr[1], ctr[3])
+    const unsigned long long* maxerr;   // precision forms: max |s_lowprec - s_fp64| (bits)
+    int b;                    // problem of the list
 };
+
+// Outcome of one list, as a discover_status: the capacities held, the
+// selection is complete and the targets were usable.
+__host__ __device__ inline int list_status(const ListCheck& c, const int64_t* r,
+                                           const unsigned long long* ctr) {
+    if ((ctr[0] & 0xFFFFFFFFull) != 0) return DISCOVER_E_NUMERIC;
+    if (r[4] > c.cap || (c.dedup && r[3] > c.fcap) || !(r[1] || c.K >= c.N) ||
+        (int64_t)ctr[1] > c.fix_cap || (int64_t)ctr[3] > c.fix_cap)
+        return DISCOVER_E_CAPACITY;
+    return DISCOVER_OK;
+}
 
 // Where the models of one L0 problem go: model q at sub + q * sub_ld (D row
 // indices), rmse[q], coef + q * coef_ld (D + 1 values), resid + q * ldr.
@@ -46,24 +59,90 @@ struct BandCheck {
     int64_t cap;
 };
 
+__host__ __device__ inline int band_status(const BandCheck& c, const unsigned long long* cnt) {
+    if ((int64_t)cnt[0] > c.cap || (int64_t)cnt[1] > c.cap) return DISCOVER_E_CAPACITY;
+    if (cnt[0] == 0) return DISCOVER_E_NUMERIC;
+    return DISCOVER_OK;
+}
+
+// How a public call runs.  On a stream that the caller is capturing, the
+// call is recorded with argument tables of its own (a fresh tag), nothing
+// it references can later be freed, and its outcome goes to device memory;
+// with device stats (nosync) it runs without waiting for the stream.  The
+// previous state is restored when the call ends.
+struct CallMode {
+    discover_ctx* c;
+    bool cap, nosync;
+    std::string prev_tag;
+    CallMode(discover_ctx* ctx, bool capture, bool device_stats)
+        : c(ctx), cap(capture), nosync(device_stats), prev_tag(ctx->tag) {
+        if (cap) {
+            c->capturing = true;
+            c->caller_capture = true;
+            c->frozen = true;
+            c->tag = "#c" + std::to_string(++c->capture_seq);
+        }
+        c->nosync = nosync;
+    }
+    ~CallMode() {
+        if (cap) {
+            c->capturing = false;
+            c->caller_capture = false;
+        }
+        c->nosync = false;
+        c->tag = prev_tag;
+    }
+};
+
+// Whether work enqueued on st is being captured into a graph.
+inline bool stream_capturing(hipStream_t st) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    DSC_HIP(hipStreamIsCapturing(st, &cs));
+    if (cs == hipStreamCaptureStatusInvalidated)
+        DSC_FAIL(DISCOVER_E_HIP, "the capture on this stream has been invalidated");
+    return cs == hipStreamCaptureStatusActive;
+}
+
+// Whether p is device memory (hipMalloc); host memory, pinned or not, is not.
+inline bool device_memory(const void* p) {
+    if (!p) return false;
+    hipPointerAttribute_t a{};
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();          // plain host memory: not an error of the call
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice;
+}
+
 // Screening of every problem of a call (validated arguments).  Outside
 // capture the call synchronises and fills out_stats; while capturing it
 // records the checks instead.
 // extra_fills: more buffers to clear with the screen's own fill launch.
+// dev_stats: device memory for the stats of a call that does not wait for
+// the stream (ctx->nosync or a capture); each problem's status field then
+// reports its outcome.
 void generate_screen(discover_ctx* ctx, const discover_problem* probs, int nb,
                      const discover_screen_params& prm, const std::vector<ScreenOut>& outs,
                      discover_screen_stats* out_stats, hipStream_t st,
                      std::vector<ListCheck>* checks = nullptr,
-                     const std::vector<FillSeg>* extra_fills = nullptr);
+                     const std::vector<FillSeg>* extra_fills = nullptr,
+                     discover_screen_stats* dev_stats = nullptr);
+
+// Whether an earlier call of this shape settled the selection sizes that a
+// call without host synchronisation starts from.
+bool screen_sizes_known(discover_ctx* ctx, const discover_problem* probs, int nb,
+                        const discover_screen_params& prm);
 
 // Exhaustive L0 of every problem of a call (validated arguments).
+// dev_stats as for generate_screen.
 void l0_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D, int m,
               const std::vector<L0Out>& outs, std::vector<discover_l0_stats>& stats,
-              hipStream_t st, std::vector<BandCheck>* checks = nullptr);
+              hipStream_t st, std::vector<BandCheck>* checks = nullptr,
+              discover_l0_stats* dev_stats = nullptr);
 
 // Orthogonal matching pursuit of every problem of a call (validated
 // arguments); problem b starts from the n_init rows init_active + b *
-// init_ld.  Outside capture the call synchronises.
+// init_ld.  The call does not wait for the stream.
 void omp_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D_max,
                const int32_t* init_active, int n_init, int64_t init_ld, int32_t* out_active,
                double* out_coef, double* out_rmse, double* out_resid, int64_t ldr, hipStream_t st);

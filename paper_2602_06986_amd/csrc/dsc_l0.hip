@@ -1325,7 +1325,7 @@ static std::shared_ptr<L0Items> l0_items(discover_ctx* ctx, int S, int D) {
     } else {
         P->items3 = sweep3_blocks(S);
     }
-    if (ctx->plans.size() >= 64) ctx->plans.clear();
+    ctx->evict_plans(64);
     ctx->plans[key] = P;
     return P;
 }
@@ -1354,9 +1354,23 @@ static size_t band_arena_bytes(const std::vector<int>& act, const std::vector<in
 }
 
 // Exhaustive L0 of every problem of a call, one launch per phase.
+// Stats of a call that did not wait for the stream (one thread per problem).
+__global__ __launch_bounds__(256) void k_l0_stats(ctab<BandCheck> B, ctab<discover_l0_stats> base, int nb,
+                                                  discover_l0_stats* __restrict__ out) {
+    const int b = blockIdx.x * 256 + threadIdx.x;
+    if (b >= nb) return;
+    const BandCheck& c = tab(B, b);
+    DSC_GLOBAL(c.cnt);
+    discover_l0_stats s = tab(base, b);
+    s.n_band = (int64_t)c.cnt[0];
+    s.status = band_status(c, c.cnt);
+    out[b] = s;
+}
+
 void l0_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D, int m,
               const std::vector<L0Out>& outs, std::vector<discover_l0_stats>& stats,
-              hipStream_t st, std::vector<BandCheck>* checks) {
+              hipStream_t st, std::vector<BandCheck>* checks, discover_l0_stats* dev_stats) {
+    const bool devmode = ctx->capturing || ctx->nosync;
     // 1. layout
     std::vector<std::shared_ptr<L0Items>> its(nb);
     std::vector<PrepArgs> pa(nb);
@@ -1407,9 +1421,8 @@ void l0_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D
     std::vector<int64_t> cap(nb, std::max<int64_t>(1 << 16, 256 * (int64_t)m));
     std::string ck((const char*)&D, sizeof D);
     ck.append((const char*)&m, sizeof m);
-    for (int b = 0; b < nb; b++) {
-        const int64_t f[5] = {probs[b].n, probs[b].S, (int64_t)(intptr_t)probs[b].F,
-                              (int64_t)(intptr_t)probs[b].y, (int64_t)(intptr_t)probs[b].ids};
+    for (int b = 0; b < nb; b++) {                      // the call's shape, not its data
+        const int32_t f[2] = {probs[b].n, probs[b].S};
         ck.append((const char*)f, sizeof f);
     }
     auto mit = ctx->batches.find("band" + ck);
@@ -1508,6 +1521,7 @@ void l0_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D
     double* rscratch = ctx->buf<double>("l0_refit_scratch", (size_t)NREFIT * sld);
     int64_t* boff = ctx->buf<int64_t>("l0_boff" + ctx->tag, (size_t)nb + 1);
     bool prefilled = true;                      // the first round's counters: cleared by k_l0_prep
+    std::vector<BandCheck> bcl;
     while (!act.empty()) {
         const int na = (int)act.size();
         std::vector<std::vector<size_t>> bo;
@@ -1575,9 +1589,9 @@ void l0_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D
         }
         k_rank_models<<<na, 256, 0, st>>>(dfa);
         check_launch("k_rank_models");
-        if (ctx->capturing) {                   // capacities are checked after the replay
-            if (checks)
-                for (int q = 0; q < na; q++) checks->push_back(BandCheck{ba[q].bcnt, cap[act[q]]});
+        if (devmode) {                          // capacities are checked on the device
+            for (int q = 0; q < na; q++) bcl.push_back(BandCheck{ba[q].bcnt, cap[act[q]]});
+            if (checks) checks->insert(checks->end(), bcl.begin(), bcl.end());
             break;
         }
         std::vector<unsigned long long> cnt(2 * (size_t)na);
@@ -1597,15 +1611,22 @@ void l0_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D
         }
         act.swap(next);
     }
-    if (!ctx->capturing) {
-        std::vector<int> all(nb);
-        for (int b = 0; b < nb; b++) all[b] = b;
-        ctx->raw("l0_band_arena" + ctx->tag, band_arena_bytes(all, cap, D, m, nullptr));
-        auto bm = std::make_shared<BandMemo>();
-        bm->cap = cap;
-        if (ctx->batches.size() >= 256) ctx->batches.clear();
-        ctx->batches["band" + ck] = bm;
+    if (devmode) {
+        if (dev_stats) {
+            k_l0_stats<<<(unsigned)cdiv(nb, 256), 256, 0, st>>>(ct(ctx->upload("l0_stats_chk", bcl, st)),
+                                                               ct(ctx->upload("l0_stats_base", stats, st)),
+                                                               nb, dev_stats);
+            check_launch("k_l0_stats");
+        }
+        return;
     }
+    std::vector<int> all(nb);
+    for (int b = 0; b < nb; b++) all[b] = b;
+    ctx->raw("l0_band_arena" + ctx->tag, band_arena_bytes(all, cap, D, m, nullptr));
+    auto bm = std::make_shared<BandMemo>();
+    bm->cap = cap;
+    if (ctx->batches.size() >= 256) ctx->batches.clear();
+    ctx->batches["band" + ck] = bm;
 }
 
 }  // namespace dsc
@@ -1648,8 +1669,13 @@ extern "C" discover_status discover_l0_fit(discover_ctx* ctx, const discover_l0_
             outs[b] = L0Out{out_subsets + (int64_t)b * m * D, D, out_rmse + (int64_t)b * m,
                             out_coef + (int64_t)b * m * (D + 1), D + 1,
                             out_resid ? out_resid + (int64_t)b * m * ldr : nullptr, ldr};
-        l0_batch(ctx, probs, n_problems, D, m, outs, stats, st);
-        if (!ctx->capturing) {
+        const bool cap = stream_capturing(st);
+        const bool dev = device_memory(out_stats);
+        DSC_REQUIRE(!cap || dev, "a call captured into a graph reports its outcome in device memory: "
+                                 "out_stats must be a device pointer");
+        CallMode mode(ctx, cap, dev);
+        l0_batch(ctx, probs, n_problems, D, m, outs, stats, st, nullptr, dev ? out_stats : nullptr);
+        if (!dev) {
             DSC_HIP(hipStreamSynchronize(st));
             ctx->resolve_timing();
             if (out_stats)
@@ -1696,10 +1722,6 @@ void omp_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int 
         }
         check_launch("omp");
     }
-    if (!ctx->capturing) {
-        DSC_HIP(hipStreamSynchronize(st));
-        ctx->resolve_timing();
-    }
 }
 
 }  // namespace dsc
@@ -1724,7 +1746,9 @@ extern "C" discover_status discover_omp(discover_ctx* ctx, const discover_l0_pro
             DSC_REQUIRE(!out_resid || ldr >= p.n, "problem %d: ldr < n", b);
         }
         DSC_HIP(hipSetDevice(ctx->device));
+        const hipStream_t st = (hipStream_t)stream;
+        CallMode mode(ctx, stream_capturing(st), false);
         omp_batch(ctx, probs, n_problems, D_max, init_active, n_init, n_init, out_active, out_coef,
-                  out_rmse, out_resid, ldr, (hipStream_t)stream);
+                  out_rmse, out_resid, ldr, st);
     });
 }

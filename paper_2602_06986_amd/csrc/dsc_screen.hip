@@ -2273,10 +2273,7 @@ static std::shared_ptr<Plan> get_plan(discover_ctx* ctx, const discover_problem&
     auto it = ctx->plans.find(key);
     if (it != ctx->plans.end()) return std::static_pointer_cast<Plan>(it->second);
     if (ctx->capturing) DSC_FAIL(DISCOVER_E_CAPACITY, "search-space plan built during graph capture");
-    if (ctx->plans.size() >= 64) {
-        ctx->plans.clear();
-        ctx->generation++;
-    }
+    ctx->evict_plans(64);
     auto P = std::make_shared<Plan>();
     P->key = key;
     Space& sp = P->sp;
@@ -2996,16 +2993,54 @@ struct SelMemo {
     std::vector<int64_t> K, cap, fcap;
 };
 
+// The shape of a call (parameters, sizes, units; not the data): the key of
+// its remembered capacities.
 static std::string call_key(const discover_problem* probs, int nb, const discover_screen_params& prm) {
     std::string k((const char*)&prm, sizeof prm);
     for (int b = 0; b < nb; b++) {
         const discover_problem& p = probs[b];
-        const int64_t f[8] = {p.n, p.p, p.T, p.B, (int64_t)(intptr_t)p.X, (int64_t)(intptr_t)p.Y,
-                              (int64_t)(intptr_t)p.exclude, p.n_exclude};
+        const int64_t f[5] = {p.n, p.p, p.T, p.B, p.n_exclude};
         k.append((const char*)f, sizeof f);
         if (p.B && p.units) k.append((const char*)p.units, sizeof(int32_t) * p.p * p.B);
     }
     return k;
+}
+
+bool screen_sizes_known(discover_ctx* ctx, const discover_problem* probs, int nb,
+                        const discover_screen_params& prm) {
+    return ctx->batches.count("sel" + call_key(probs, nb, prm)) != 0;
+}
+
+// Host-known counters of one problem and where its lists' checks start.
+struct StatBase {
+    discover_screen_stats s;
+    int32_t l0, nl;
+};
+
+// Stats of a call that did not wait for the stream: one thread per problem
+// folds its lists' outcomes into the counters and the status.
+__global__ __launch_bounds__(256) void k_screen_stats(ctab<StatBase> base, ctab<ListCheck> L, int nb,
+                                                      discover_screen_stats* __restrict__ out) {
+    const int b = blockIdx.x * 256 + threadIdx.x;
+    if (b >= nb) return;
+    const StatBase& B = tab(base, b);
+    discover_screen_stats s = B.s;
+    int status = DISCOVER_OK;
+    for (int l = B.l0; l < B.l0 + B.nl; l++) {
+        const ListCheck& c = tab(L, l);
+        const int64_t* r = c.res;
+        const unsigned long long* ctr = c.ctr;
+        DSC_GLOBAL(r); DSC_GLOBAL(ctr); DSC_GLOBAL(c.maxerr);
+        const int v = list_status(c, r, ctr);
+        if (status == DISCOVER_OK) status = v;
+        s.n_scored = (int64_t)ctr[2];
+        s.pool_size += r[4];
+        s.n_selected += r[0];
+        s.n_merged += r[2];
+        s.max_lowprec_err = fmax(s.max_lowprec_err, __longlong_as_double((long long)*c.maxerr));
+    }
+    s.status = status;
+    out[b] = s;
 }
 
 struct FixRegrow {
@@ -3015,7 +3050,11 @@ struct FixRegrow {
 static void generate_screen_once(discover_ctx* ctx, const discover_problem* probs, int nb,
                                  const discover_screen_params& prm, const std::vector<ScreenOut>& outs,
                                  discover_screen_stats* out_stats, hipStream_t st,
-                                 std::vector<ListCheck>* checks, const std::vector<FillSeg>* extra_fills) {
+                                 std::vector<ListCheck>* checks, const std::vector<FillSeg>* extra_fills,
+                                 discover_screen_stats* dev_stats) {
+    // without host synchronisation one selection round runs at the sizes
+    // an earlier call settled on, and its outcome is judged on the device
+    const bool devmode = ctx->capturing || ctx->nosync;
     std::vector<Problem> PS;
     std::vector<ListState> LS;
     std::vector<int> act;
@@ -3068,6 +3107,7 @@ static void generate_screen_once(discover_ctx* ctx, const discover_problem* prob
         }
     }
     std::vector<SelArgs> sa;
+    std::vector<ListCheck> lc;
     bool checked_bad = false;
     bool prefilled = true;
     int rounds = 0;
@@ -3075,13 +3115,13 @@ static void generate_screen_once(discover_ctx* ctx, const discover_problem* prob
         select_round(ctx, probs, prm, PS, LS, act, margin, outs, st, sa, prefilled);
         prefilled = false;
         rounds++;
-        if (ctx->capturing) {                   // results are checked after the replay
-            if (checks)
-                for (size_t q = 0; q < act.size(); q++) {
-                    const ListState& L = LS[act[q]];
-                    checks->push_back(ListCheck{sa[q].res, L.cap, L.fcap, L.K, PS[L.b].N,
-                                                PS[L.b].ctr, prm.dedup, PS[L.b].fix_cap});
-                }
+        if (devmode) {                          // results are checked on the device
+            for (size_t q = 0; q < act.size(); q++) {
+                const ListState& L = LS[act[q]];
+                lc.push_back(ListCheck{sa[q].res, L.cap, L.fcap, L.K, PS[L.b].N, PS[L.b].ctr, prm.dedup,
+                                       PS[L.b].fix_cap, sa[q].maxerr, L.b});
+            }
+            if (checks) checks->insert(checks->end(), lc.begin(), lc.end());
             break;
         }
         // one synchronisation per round: outcome of every active list
@@ -3150,7 +3190,7 @@ static void generate_screen_once(discover_ctx* ctx, const discover_problem* prob
         act.swap(next);
     }
     const auto gen0 = ctx->generation;
-    if (!ctx->capturing) {
+    if (!devmode) {
         // size the result arena for a one-round run of every list at the final
         // capacities, as a captured run does
         select_reserve(ctx, prm, LS);
@@ -3181,21 +3221,37 @@ static void generate_screen_once(discover_ctx* ctx, const discover_problem* prob
         k_values<<<dim3((unsigned)cdiv(mmax, 4), nb), 256, 0, st>>>(ct(ctx->upload("scr_values", va, st)));
         check_launch("k_values");
     }
-    if (!ctx->capturing) {
-        DSC_HIP(hipStreamSynchronize(st));
-        ctx->resolve_timing();
-        if (out_stats)
-            for (int b = 0; b < nb; b++) out_stats[b] = stats[b];
+    if (devmode) {
+        if (dev_stats) {
+            // lists are laid out problem by problem
+            std::vector<StatBase> sb(nb);
+            for (int b = 0; b < nb; b++) { sb[b].s = stats[b]; sb[b].l0 = -1; sb[b].nl = 0; }
+            for (size_t l = 0; l < lc.size(); l++) {
+                StatBase& x = sb[lc[l].b];
+                if (x.l0 < 0) x.l0 = (int32_t)l;
+                x.nl++;
+            }
+            for (StatBase& x : sb) x.l0 = std::max(x.l0, 0);
+            k_screen_stats<<<(unsigned)cdiv(nb, 256), 256, 0, st>>>(
+                ct(ctx->upload("scr_stats_base", sb, st)), ct(ctx->upload("scr_stats_lists", lc, st)), nb,
+                dev_stats);
+            check_launch("k_screen_stats");
+        }
+        return;
     }
+    DSC_HIP(hipStreamSynchronize(st));
+    ctx->resolve_timing();
+    if (out_stats)
+        for (int b = 0; b < nb; b++) out_stats[b] = stats[b];
 }
 
 void generate_screen(discover_ctx* ctx, const discover_problem* probs, int nb,
                      const discover_screen_params& prm, const std::vector<ScreenOut>& outs,
                      discover_screen_stats* out_stats, hipStream_t st, std::vector<ListCheck>* checks,
-                     const std::vector<FillSeg>* extra_fills) {
+                     const std::vector<FillSeg>* extra_fills, discover_screen_stats* dev_stats) {
     for (;;) {
         try {
-            generate_screen_once(ctx, probs, nb, prm, outs, out_stats, st, checks, extra_fills);
+            generate_screen_once(ctx, probs, nb, prm, outs, out_stats, st, checks, extra_fills, dev_stats);
             return;
         } catch (const FixRegrow& r) {
             if (r.need >= ((int64_t)1 << 40))
@@ -3217,6 +3273,11 @@ extern "C" discover_status discover_generate_screen(discover_ctx* ctx, const dis
         DSC_REQUIRE(ctx, "ctx is NULL");
         validate(probs, n_problems, prm, out_ids, out_scores, out_values, ldv);
         DSC_HIP(hipSetDevice(ctx->device));
+        const hipStream_t st = (hipStream_t)stream;
+        const bool cap = stream_capturing(st);
+        const bool dev = device_memory(out_stats);
+        DSC_REQUIRE(!cap || dev, "a call captured into a graph reports its outcome in device memory: "
+                                 "out_stats must be a device pointer");
         std::vector<ScreenOut> outs(n_problems);
         int64_t row = 0;
         for (int b = 0; b < n_problems; b++) {
@@ -3224,6 +3285,20 @@ extern "C" discover_status discover_generate_screen(discover_ctx* ctx, const dis
                                 out_values ? out_values + row * prm->k * ldv : nullptr, ldv};
             row += prm->score_mode == DISCOVER_SCORE_MAX ? 1 : probs[b].T;
         }
-        generate_screen(ctx, probs, n_problems, *prm, outs, out_stats, (hipStream_t)stream);
+        if (dev && !screen_sizes_known(ctx, probs, n_problems, *prm)) {
+            if (cap)
+                DSC_FAIL(DISCOVER_E_CAPACITY, "no call of this shape has run outside capture: run it "
+                                              "once (or discover_reserve) before capturing");
+            // the first call of a shape settles its sizes, waiting for the stream
+            std::vector<discover_screen_stats> hs(n_problems);
+            generate_screen(ctx, probs, n_problems, *prm, outs, hs.data(), st);
+            DSC_HIP(hipMemcpyAsync(out_stats, hs.data(), hs.size() * sizeof(discover_screen_stats),
+                                   hipMemcpyHostToDevice, st));
+            DSC_HIP(hipStreamSynchronize(st));
+            return;
+        }
+        CallMode mode(ctx, cap, dev);
+        generate_screen(ctx, probs, n_problems, *prm, outs, dev ? nullptr : out_stats, st, nullptr, nullptr,
+                        dev ? out_stats : nullptr);
     });
 }
