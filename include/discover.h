@@ -275,6 +275,26 @@ discover_status discover_omp(discover_ctx* ctx, const discover_l0_problem* probs
                              int32_t* out_active, double* out_coef, double* out_rmse,
                              double* out_resid, int64_t ldr, void* stream);
 
+/* discover_omp for callers that cannot allocate device memory (code under
+ * graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same arguments, kernels and results, with the work buffers taken
+ * from a fixed 64 MiB device array that the library holds on each GPU it
+ * runs on (set up by discover_create) until the process ends.  The call
+ * allocates nothing and creates no events; it does not wait for the
+ * stream.  Work space per problem, in bytes (each term rounded up to 256):
+ * 8 (S + 1) ceil16(n) + 2 (8 S) + 8 (D_max + 2) n, + 8 n when out_resid is
+ * NULL, + 768; a call whose problems need more than 64 MiB in total fails with
+ * E_ARG before any launch.  Every call on a GPU uses that GPU's one array
+ * (whatever the context), so calls that overlap in time on one GPU, on
+ * different streams or from different threads, race: order them.  Nothing
+ * in the array needs to start at zero; it keeps the last call's contents.
+ * Errors: as discover_omp. */
+discover_status discover_omp_noalloc(discover_ctx* ctx, const discover_l0_problem* probs,
+                                     int32_t n_problems, int32_t D_max,
+                                     const int32_t* init_active, int32_t n_init,
+                                     int32_t* out_active, double* out_coef, double* out_rmse,
+                                     double* out_resid, int64_t ldr, void* stream);
+
 /* The SISSO loop (cited SISSO method, Summary; iterative generation ->
  * screening -> sparsifying, Software Description) over a batch of datasets
  * of uneven n and p, as one sequence of batched launches: for d = 1..D

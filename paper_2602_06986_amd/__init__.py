@@ -69,7 +69,7 @@ SYMBOLS = ("discover_create", "discover_destroy", "discover_last_error",
            "discover_generate_screen", "discover_l0_fit", "discover_omp", "discover_count",
            "discover_decode", "discover_set_timing", "discover_timing", "discover_reset_timing",
            "discover_sisso_batch", "discover_set_graph_timing", "discover_set_fixup_capacity",
-           "discover_reserve")
+           "discover_reserve", "discover_omp_noalloc")
 
 _lib = None
 
@@ -95,6 +95,7 @@ def lib():
                                        C.c_int32, C.c_int32, P]
         L.discover_omp.argtypes = [P, C.POINTER(L0Problem), C.c_int32, C.c_int32, P, C.c_int32,
                                    P, P, P, P, C.c_int64, P]
+        L.discover_omp_noalloc.argtypes = L.discover_omp.argtypes
         L.discover_count.argtypes = [C.c_int32, C.POINTER(ScreenParams)]
         L.discover_count.restype = C.c_int64
         L.discover_decode.argtypes = [C.c_int32, C.POINTER(ScreenParams), C.c_int64, C.c_char_p,
@@ -327,7 +328,12 @@ class Context:
         ((sub, rmse, coef, res, st),) = self.l0_fit_batch([F], [ids], [y], D, m, resid, device_stats)
         return sub, rmse, coef, res, st
 
-    def omp(self, F, ids, y, D_max, init=None):
+    def omp_noalloc(self, F, ids, y, D_max, init=None):
+        """``omp`` through the allocation-free entry point (work space in the
+        library's fixed per-GPU array; the outputs are allocated here)."""
+        return self.omp(F, ids, y, D_max, init, _fn="discover_omp_noalloc")
+
+    def omp(self, F, ids, y, D_max, init=None, _fn="discover_omp"):
         """OMP over the rows of F from the warm start ``init`` (int32 CUDA
         tensor of rows, or None).  Returns (active [D_max], coef [D_max+1],
         rmse, resid [n])."""
@@ -349,9 +355,9 @@ class Context:
             init = init.to(torch.int32).contiguous()
             n_init = init.numel()
             ip = init.data_ptr()
-        _check(lib().discover_omp(self.h, C.byref(pb), 1, D_max, ip, n_init, act.data_ptr(),
-                                  coef.data_ptr(), rmse.data_ptr(), res.data_ptr(), n,
-                                  _stream_handle(torch, dev)))
+        _check(getattr(lib(), _fn)(self.h, C.byref(pb), 1, D_max, ip, n_init, act.data_ptr(),
+                                   coef.data_ptr(), rmse.data_ptr(), res.data_ptr(), n,
+                                   _stream_handle(torch, dev)))
         return act, coef, rmse, res
 
     # ------------------------------------------------------------ loop

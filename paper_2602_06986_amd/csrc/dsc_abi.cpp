@@ -1,4 +1,5 @@
 // Context lifetime, error text, host-side space queries and kernel timing.
+#include "dsc_internal.h"
 #include "dsc_space.h"
 
 extern "C" discover_status discover_create(int device, discover_ctx** out) {
@@ -10,6 +11,7 @@ extern "C" discover_status discover_create(int device, discover_ctx** out) {
         DSC_HIP(hipGetDeviceCount(&count));
         DSC_REQUIRE(device >= 0 && device < count, "device %d outside 0..%d", device, count - 1);
         DSC_HIP(hipSetDevice(device));
+        noalloc_init(device);              // this device's copy of the OMP scratch
         discover_ctx* c = new discover_ctx();
         c->device = device;
         *out = c;

@@ -143,8 +143,18 @@ void l0_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D
 // Orthogonal matching pursuit of every problem of a call (validated
 // arguments); problem b starts from the n_init rows init_active + b *
 // init_ld.  The call does not wait for the stream.
+// With scratch (omp_scratch_bytes bytes of device memory) the call takes
+// its work buffers from there and allocates and creates nothing.
 void omp_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D_max,
                const int32_t* init_active, int n_init, int64_t init_ld, int32_t* out_active,
-               double* out_coef, double* out_rmse, double* out_resid, int64_t ldr, hipStream_t st);
+               double* out_coef, double* out_rmse, double* out_resid, int64_t ldr, hipStream_t st,
+               char* scratch = nullptr);
+// Looks up this device's address of the allocation-free OMP's scratch
+// (the device must be current).
+void noalloc_init(int device);
+size_t omp_scratch_bytes(const discover_l0_problem* probs, int nb, int D_max, bool resid);
+void validate_omp(const discover_l0_problem* probs, int32_t n_problems, int32_t D_max,
+                  const int32_t* init_active, int32_t n_init, const int32_t* out_active,
+                  const double* out_coef, const double* out_rmse, const double* out_resid, int64_t ldr);
 
 }  // namespace dsc

@@ -1686,24 +1686,65 @@ extern "C" discover_status discover_l0_fit(discover_ctx* ctx, const discover_l0_
 
 namespace dsc {
 
+// Work buffers of one problem's OMP (byte sizes, each a multiple of 256):
+// standardised rows Z, |y - mean|^2, active count, scores, row norms,
+// residual (when the caller keeps none), QR columns, RSS.
+static void omp_sizes(const discover_l0_problem& pb, int D_max, bool resid, size_t sz[8]) {
+    auto r256 = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t ldz = (size_t)cdiv(pb.n, 16) * 16;
+    sz[0] = r256((size_t)(pb.S + 1) * ldz * 8);
+    sz[1] = 256;
+    sz[2] = 256;
+    sz[3] = r256((size_t)pb.S * 8);
+    sz[4] = r256((size_t)pb.S * 8);
+    sz[5] = resid ? 0 : r256((size_t)pb.n * 8);
+    sz[6] = r256((size_t)(D_max + 2) * pb.n * 8);
+    sz[7] = 256;
+}
+
+size_t omp_scratch_bytes(const discover_l0_problem* probs, int nb, int D_max, bool resid) {
+    size_t t = 0;
+    for (int b = 0; b < nb; b++) {
+        size_t sz[8];
+        omp_sizes(probs[b], D_max, resid, sz);
+        for (size_t v : sz) t += v;
+    }
+    return t;
+}
+
 void omp_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D_max,
                const int32_t* init_active, int n_init, int64_t init_ld, int32_t* out_active,
-               double* out_coef, double* out_rmse, double* out_resid, int64_t ldr, hipStream_t st) {
+               double* out_coef, double* out_rmse, double* out_resid, int64_t ldr, hipStream_t st,
+               char* scratch) {
+    static const char* const names[8] = {"ompZ", "ompyy", "ompn", "ompg", "ompnrm", "ompr", "ompA", "omprss"};
+    size_t off = 0;
     for (int b = 0; b < nb; b++) {
         const discover_l0_problem& pb = probs[b];
-        const std::string sfx = std::to_string(b);
         const int ldz = (int)cdiv(pb.n, 16) * 16;
-        double* Z = ctx->buf<double>("ompZ" + sfx, (size_t)(pb.S + 1) * ldz);
-        double* yy = ctx->buf<double>("ompyy" + sfx, 1);
+        size_t sz[8];
+        omp_sizes(pb, D_max, out_resid != nullptr, sz);
+        char* w[8] = {};
+        for (int q = 0; q < 8; q++) {
+            if (!sz[q]) continue;
+            if (scratch) {                       // the caller's scratch, laid out in order
+                w[q] = scratch + off;
+                off += sz[q];
+            } else {
+                w[q] = (char*)ctx->raw(names[q] + std::to_string(b), sz[q]);
+            }
+        }
+        double* Z = (double*)w[0];
+        double* yy = (double*)w[1];
         int32_t* active = out_active + (int64_t)b * D_max;
-        int32_t* nact = ctx->buf<int32_t>("ompn" + sfx, 1);
-        double* g = ctx->buf<double>("ompg" + sfx, pb.S);
-        double* nrm = ctx->buf<double>("ompnrm" + sfx, pb.S);
-        double* r = out_resid ? out_resid + (int64_t)b * ldr : ctx->buf<double>("ompr" + sfx, pb.n);
-        double* A = ctx->buf<double>("ompA" + sfx, (size_t)(D_max + 2) * pb.n);
-        double* rss = ctx->buf<double>("omprss" + sfx, 1);
+        int32_t* nact = (int32_t*)w[2];
+        double* g = (double*)w[3];
+        double* nrm = (double*)w[4];
+        double* r = out_resid ? out_resid + (int64_t)b * ldr : (double*)w[5];
+        double* A = (double*)w[6];
+        double* rss = (double*)w[7];
         double* coef = out_coef + (int64_t)b * (D_max + 1);
-        KTimer kt(ctx, st, "omp");
+        // (no timer events in the scratch form: it creates nothing)
+        std::unique_ptr<KTimer> kt(scratch ? nullptr : new KTimer(ctx, st, "omp"));
         k_omp_prep<<<(unsigned)cdiv(pb.S + 1, 4), 256, 0, st>>>(
             pb.n, pb.S, pb.F, pb.ldf, pb.y, ldz, Z, yy, nrm, active, D_max,
             n_init ? init_active + (int64_t)b * init_ld : nullptr, n_init, nact);
@@ -1724,6 +1765,22 @@ void omp_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int 
     }
 }
 
+void validate_omp(const discover_l0_problem* probs, int32_t n_problems, int32_t D_max,
+                  const int32_t* init_active, int32_t n_init, const int32_t* out_active,
+                  const double* out_coef, const double* out_rmse, const double* out_resid, int64_t ldr) {
+    DSC_REQUIRE(probs && n_problems >= 1, "probs/n_problems");
+    DSC_REQUIRE(D_max >= 1 && D_max <= DISCOVER_MAX_D, "D_max = %d outside 1..%d", D_max, DISCOVER_MAX_D);
+    DSC_REQUIRE(n_init >= 0 && n_init <= D_max && (n_init == 0 || init_active), "init_active");
+    DSC_REQUIRE(out_active && out_coef && out_rmse, "outputs required");
+    for (int b = 0; b < n_problems; b++) {
+        const discover_l0_problem& p = probs[b];
+        DSC_REQUIRE(p.S >= D_max, "problem %d: S = %d < D_max", b, p.S);
+        DSC_REQUIRE(p.n >= D_max + 2, "problem %d: n too small", b);
+        DSC_REQUIRE(p.F && p.ids && p.y && p.ldf >= p.n, "problem %d: F/ids/y/ldf", b);
+        DSC_REQUIRE(!out_resid || ldr >= p.n, "problem %d: ldr < n", b);
+    }
+}
+
 }  // namespace dsc
 
 extern "C" discover_status discover_omp(discover_ctx* ctx, const discover_l0_problem* probs,
@@ -1733,18 +1790,9 @@ extern "C" discover_status discover_omp(discover_ctx* ctx, const discover_l0_pro
                                         void* stream) {
     using namespace dsc;
     return guarded([&] {
-        DSC_REQUIRE(ctx && probs && n_problems >= 1, "ctx/probs");
-        DSC_REQUIRE(D_max >= 1 && D_max <= DISCOVER_MAX_D, "D_max = %d outside 1..%d", D_max,
-                    DISCOVER_MAX_D);
-        DSC_REQUIRE(n_init >= 0 && n_init <= D_max && (n_init == 0 || init_active), "init_active");
-        DSC_REQUIRE(out_active && out_coef && out_rmse, "outputs required");
-        for (int b = 0; b < n_problems; b++) {
-            const discover_l0_problem& p = probs[b];
-            DSC_REQUIRE(p.S >= D_max, "problem %d: S = %d < D_max", b, p.S);
-            DSC_REQUIRE(p.n >= D_max + 2, "problem %d: n too small", b);
-            DSC_REQUIRE(p.F && p.ids && p.y && p.ldf >= p.n, "problem %d: F/ids/y/ldf", b);
-            DSC_REQUIRE(!out_resid || ldr >= p.n, "problem %d: ldr < n", b);
-        }
+        DSC_REQUIRE(ctx, "ctx is NULL");
+        validate_omp(probs, n_problems, D_max, init_active, n_init, out_active, out_coef, out_rmse,
+                     out_resid, ldr);
         DSC_HIP(hipSetDevice(ctx->device));
         const hipStream_t st = (hipStream_t)stream;
         CallMode mode(ctx, stream_capturing(st), false);
