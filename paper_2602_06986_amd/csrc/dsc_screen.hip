@@ -1465,113 +1465,40 @@ __device__ __forceinline__ void d_scatter(const double* __restrict__ ps,
     }
 }
 
-// Near-tie window of each sorted entry: lo[q] = first earlier position whose
-// score is within TAU_NEAR (relative) of entry q, scanning backwards.
-__device__ __forceinline__ void d_window(const double* __restrict__ ss,
-                                         const unsigned long long* __restrict__ Pp, int64_t cap,
-                                         int32_t* __restrict__ lo, int32_t* __restrict__ cnt) {
+// Near-tie clusters of the sorted pool.  Entries q-1 and q are chained when
+// ss[q-1] - ss[q] <= TAU_NEAR ss[q-1]; a cluster is a maximal chain.  A
+// group head h can only take entries of its own cluster: across a break,
+// ss[h] - ss[q] exceeds TAU_NEAR ss[h].  Every valid entry starts as its own
+// head (parent[q] = q; -3 for an entry whose exact score is not positive),
+// and the start of every cluster of two or more entries is listed for
+// k_dedup (count in *ncl).
+__device__ __forceinline__ bool chained(const double* __restrict__ ss, int64_t q) {
+    const double sp = ss[q - 1], s = ss[q];
+    return s > 0.0 && sp - s <= TAU_NEAR * sp;
+}
+
+__device__ __forceinline__ void d_clusters(const double* __restrict__ ss,
+                                           const unsigned long long* __restrict__ Pp, int64_t cap,
+                                           int dedup, int32_t* __restrict__ parent,
+                                           int32_t* __restrict__ starts,
+                                           unsigned long long* __restrict__ ncl) {
     const int64_t P = min((int64_t)*Pp, cap);
-    // The window of q is the run of earlier positions l' (at most 1024 back)
-    // whose scores pass sp - s <= TAU_NEAR * sp.  Scores descend, and for
-    // s <= sp <= 2 s the difference is exact, so the test holds on a suffix
-    // of positions before q: a galloping search (1, 2, 4, ... back) brackets
-    // its start and a bisection finds it, in O(log window) loads.
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < P;
          q += (int64_t)gridDim.x * blockDim.x) {
-        const double s = ss[q];
-        int64_t l = q;
-        if (s > 0.0) {
-            const int64_t lim = q >= 1024 ? q - 1024 : 0;
-            int64_t good = q, bad = lim - 1;          // the test holds on [good, q), fails at bad
-            for (int64_t step = 1;; step *= 2) {
-                const int64_t c = q - step;
-                if (c < lim) break;
-                const double sp = ss[c];
-                if (sp - s <= TAU_NEAR * sp) {
-                    good = c;
-                } else {
-                    bad = c;
-                    break;
-                }
-            }
-            while (good - bad > 1) {
-                const int64_t mid = bad + (good - bad) / 2;
-                const double sp = ss[mid];
-                if (sp - s <= TAU_NEAR * sp) good = mid; else bad = mid;
-            }
-            l = good;
-        }
-        lo[q] = (int32_t)l;
-        cnt[q] = (int32_t)(q - l);
+        const bool valid = ss[q] > 0.0;
+        parent[q] = valid ? (int32_t)q : -3;
+        if (dedup && valid && (q == 0 || !chained(ss, q)) && q + 1 < P && chained(ss, q + 1))
+            starts[atomicAdd(ncl, 1ull)] = (int32_t)q;
     }
 }
 
-// Exclusive prefix sum of cnt (one block of 1024 threads): each thread sums
-// a contiguous chunk, the chunk sums are scanned across the block, then
-// each thread writes its chunk's offsets.
-__device__ __forceinline__ int64_t block_excl_scan1024(int64_t v, int64_t* part) {
-    const int t = threadIdx.x;
-    part[t] = v;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        const int64_t x = t >= o ? part[t - o] : 0;
-        __syncthreads();
-        part[t] += x;
-        __syncthreads();
-    }
-    const int64_t incl = part[t];
-    __syncthreads();
-    return incl - v;
-}
-
-__device__ __forceinline__ void d_scan_offsets(const int32_t* __restrict__ cnt,
-                                               const unsigned long long* __restrict__ Pp,
-                                               int64_t cap, int64_t* __restrict__ off) {
-    const int64_t P = min((int64_t)*Pp, cap);
-    __shared__ int64_t part[1024];
-    const int64_t per = (P + 1023) / 1024;
-    const int64_t b = threadIdx.x * per, e = min(P, b + per);
-    int64_t s = 0;
-    for (int64_t q = b; q < e; q++) s += cnt[q];
-    int64_t acc = block_excl_scan1024(s, part);
-    if (threadIdx.x == 1023) off[P] = acc + s;
-    for (int64_t q = b; q < e; q++) {
-        off[q] = acc;
-        acc += cnt[q];
-    }
-}
-
-// One wave per near-tie pair (earlier position lo[q]+k, later position q):
-// duplicate flag = |corr| >= 1 - TAU_DUP.  Pairs of stored pool entries
-// take the stored values, means and sums of squares (the same numbers the
-// two-pass evaluation below forms, in the same order); others evaluate
-// both candidates.
-__device__ __forceinline__ void d_pairs(const int64_t* __restrict__ pool,
-                                               const int32_t* __restrict__ order,
-                                               const int32_t* __restrict__ lo,
-                                               const int64_t* __restrict__ off,
-                                               const unsigned long long* __restrict__ Pp, int64_t cap,
-                                               const EvalCtx& ev, Ops o, int n,
-                                               uint8_t* __restrict__ flag, int64_t flag_cap,
-                                               const PoolVals pvs) {
-    const int64_t P = min((int64_t)*Pp, cap);
-    const int64_t total = min(off[P], flag_cap);
+// |corr(u, v)| >= 1 - TAU_DUP for the pool entries at slots iu and iv (one
+// whole wave; every lane returns the flag).  Stored pool entries take the
+// stored values, means and sums of squares (the same numbers the two-pass
+// evaluation below forms, in the same order); others evaluate both.
+__device__ __forceinline__ bool dup_pair(const int64_t* __restrict__ pool, int32_t iu, int32_t iv,
+                                         const EvalCtx& ev, Ops o, int n, const PoolVals& pvs) {
     const int lane = threadIdx.x & 63;
-    for (int64_t w = (int64_t)blockIdx.x * 4 + wave_id(); w < total;
-         w += (int64_t)gridDim.x * 4) {
-    // find q with off[q] <= w < off[q+1]: 64 probes per round, the last
-    // probe at or below w narrows [a, b) to one probe step
-    int64_t a = 0, b = P;
-    while (b - a > 1) {
-        const int64_t step = (b - a + 63) / 64;
-        const int64_t idx = a + lane * step;
-        const uint64_t le = __builtin_amdgcn_ballot_w64(idx < b && off[idx] <= w);
-        a += (int64_t)(63 - __clzll((long long)le)) * step;
-        b = min(b, a + step);
-    }
-    const int64_t q = a;
-    const int64_t pe = lo[q] + (w - off[q]);
-    const int32_t iu = order[pe], iv = order[q];
     if (iu < pvs.cap && iv < pvs.cap && !isnan(pvs.sxx[iu]) && !isnan(pvs.sxx[iv])) {
         const double* u = pvs.v + (int64_t)iu * pvs.ld;
         const double* v = pvs.v + (int64_t)iv * pvs.ld;
@@ -1579,15 +1506,10 @@ __device__ __forceinline__ void d_pairs(const int64_t* __restrict__ pool,
         double uv = 0.0;
         for (int i = lane; i < n; i += 64) uv += (u[i] - mu_) * (v[i] - mv);
         uv = wave_sum(uv);
-        if (lane == 0) flag[w] = fabs(uv) / sqrt(pvs.sxx[iu] * pvs.sxx[iv]) >= 1.0 - TAU_DUP;
-        continue;
+        return fabs(uv) / sqrt(pvs.sxx[iu] * pvs.sxx[iv]) >= 1.0 - TAU_DUP;
     }
     Cand cu, cv;
-    const bool okp = cand_of_id(ev, pool[iu], cu) && cand_of_id(ev, pool[iv], cv);
-    if (!okp) {
-        if (lane == 0) flag[w] = 0;
-        continue;
-    }
+    if (!(cand_of_id(ev, pool[iu], cu) && cand_of_id(ev, pool[iv], cv))) return false;
     double su = 0.0, sv = 0.0;
     for (int i = lane; i < n; i += 64) {
         su += cand_value(cu, o, i);
@@ -1604,7 +1526,67 @@ __device__ __forceinline__ void d_pairs(const int64_t* __restrict__ pool,
     uu = wave_sum(uu);
     vv = wave_sum(vv);
     uv = wave_sum(uv);
-    if (lane == 0) flag[w] = fabs(uv) / sqrt(uu * vv) >= 1.0 - TAU_DUP;
+    return fabs(uv) / sqrt(uu * vv) >= 1.0 - TAU_DUP;
+}
+
+// Duplicate heads of the listed clusters, one cluster at a time per block
+// (blocks stride over the list).  Inside a cluster the entries are visited
+// in sorted order: an entry that no earlier head took is a head, and takes
+// every later entry of its near-tie window (ss[h] - ss[q] <= TAU_NEAR ss[h])
+// that is still free and is its duplicate.  So each entry joins the
+// earliest head in its window of which it is a duplicate, and heads only
+// are compared: a group of G equal scores costs G - 1 correlations, not a
+// window of pairs.
+__device__ __forceinline__ void d_dedup(const int64_t* __restrict__ pool, const int32_t* __restrict__ order,
+                                        const double* __restrict__ ss,
+                                        const unsigned long long* __restrict__ Pp, int64_t cap,
+                                        const EvalCtx& ev, Ops o, int n, int32_t* __restrict__ parent,
+                                        const int32_t* __restrict__ starts,
+                                        const unsigned long long* __restrict__ ncl, const PoolVals& pvs) {
+    __shared__ int64_t s_head, s_end, s_c1;
+    const int64_t P = min((int64_t)*Pp, cap);
+    const int64_t nc = (int64_t)*ncl;
+    const int w = wave_id(), nw = blockDim.x / 64;
+    volatile int32_t* vpar = parent;
+    for (int64_t c = blockIdx.x; c < nc; c += gridDim.x) {
+        if (threadIdx.x == 0) {
+            const int64_t c0 = starts[c];
+            int64_t c1 = c0 + 1;
+            while (c1 < P && chained(ss, c1)) c1++;
+            s_c1 = c1;
+            s_head = c0;
+        }
+        __syncthreads();
+        const int64_t c1 = s_c1;
+        for (;;) {
+            const int64_t h = s_head;
+            if (h >= c1) break;
+            if (threadIdx.x == 0) {              // the head's window: a prefix of (h, c1)
+                const double sh = ss[h];
+                int64_t lo = h, hi = c1;         // in window up to lo, not from hi
+                while (hi - lo > 1) {
+                    const int64_t mid = lo + (hi - lo) / 2;
+                    if (sh - ss[mid] <= TAU_NEAR * sh) lo = mid; else hi = mid;
+                }
+                s_end = lo + 1;
+            }
+            __syncthreads();
+            const int64_t e = s_end;
+            const int32_t ih = order[h];
+            for (int64_t q = h + 1 + w; q < e; q += nw) {
+                if (vpar[q] != (int32_t)q) continue;          // taken by an earlier head
+                if (dup_pair(pool, ih, order[q], ev, o, n, pvs) && (threadIdx.x & 63) == 0)
+                    vpar[q] = (int32_t)h;
+            }
+            __threadfence_block();
+            __syncthreads();
+            if (threadIdx.x == 0) {              // the next free entry heads the next group
+                int64_t q = h + 1;
+                while (q < c1 && vpar[q] != (int32_t)q) q++;
+                s_head = q;
+            }
+            __syncthreads();
+        }
     }
 }
 
@@ -1637,59 +1619,25 @@ __device__ __forceinline__ int64_t block_excl_scan(int64_t v, int64_t* part) {
 
 __device__ __forceinline__ void d_groups(
     const int64_t* __restrict__ pool, const double* __restrict__ ps, const uint8_t* __restrict__ pex,
-    const int32_t* __restrict__ order, const int32_t* __restrict__ lo, const int64_t* __restrict__ off,
-    const uint8_t* __restrict__ flag, const unsigned long long* __restrict__ Pp, int64_t cap,
-    int64_t flag_cap, int k, int dedup, const uint32_t* __restrict__ sel,
+    const int32_t* __restrict__ order, const unsigned long long* __restrict__ Pp, int64_t cap,
+    int k, const uint32_t* __restrict__ sel,
     const int64_t* __restrict__ st, double margin, int32_t* __restrict__ parent,
     int32_t* __restrict__ blk, unsigned long long* __restrict__ repid, int32_t* __restrict__ reppos,
     int32_t* __restrict__ headpos, int64_t* __restrict__ out_ids, double* __restrict__ out_sc,
     int64_t* __restrict__ res) {
     __shared__ int64_t part[GRP_THREADS];
-    __shared__ int changed, undecided;
     const int64_t P = min((int64_t)*Pp, cap);
     const int t = threadIdx.x;
     const bool all = st[1] != 0;
     const double th_scan = all ? -1.0 : select_threshold(sel, st) - margin;
-    volatile int32_t* vpar = parent;
-    // 1. initial decisions
+    const int32_t* vpar = parent;                          // heads, set by k_clusters / k_dedup
     for (int64_t q = t; q < P; q += GRP_THREADS) {
-        const double sq = ps[order[q]];
-        int32_t v = (int32_t)q;
-        if (!(sq > 0.0)) v = -3;                           // invalid after exact rescoring
-        else if (dedup) {
-            for (int64_t p2 = lo[q]; p2 < q; p2++)
-                if (off[q] + (p2 - lo[q]) < flag_cap && flag[off[q] + (p2 - lo[q])]) { v = -2; break; }
-        }
-        parent[q] = v;
         blk[q] = 0;
         repid[q] = ~0ull;
         reppos[q] = -1;
     }
     __syncthreads();
-    // 2. rounds
-    for (;;) {
-        if (t == 0) { changed = 0; undecided = 0; }
-        __syncthreads();
-        for (int64_t q = t; q < P; q += GRP_THREADS) {
-            if (vpar[q] != -2) continue;
-            int32_t dec = (int32_t)q;                       // head unless a flagged head comes first
-            bool wait = false;
-            for (int64_t p2 = lo[q]; p2 < q; p2++) {
-                if (off[q] + (p2 - lo[q]) >= flag_cap || !flag[off[q] + (p2 - lo[q])]) continue;
-                const int32_t sp2 = vpar[p2];
-                if (sp2 == -2) { wait = true; break; }
-                if (sp2 == (int32_t)p2) { dec = (int32_t)p2; break; }
-            }
-            if (wait) { atomicAdd(&undecided, 1); continue; }
-            vpar[q] = dec;
-            atomicAdd(&changed, 1);
-        }
-        __syncthreads();
-        const int ch = changed, un = undecided;
-        __syncthreads();
-        if (un == 0 || ch == 0) break;
-    }
-    // 3. aggregate groups onto their heads
+    // aggregate groups onto their heads
     int64_t merged_loc = 0;
     for (int64_t q = t; q < P; q += GRP_THREADS) {
         const int32_t h = vpar[q];
@@ -1763,7 +1711,7 @@ __device__ __forceinline__ void d_groups(
         res[0] = ns;
         res[1] = complete ? 1 : 0;
         res[2] = merged_tot;
-        res[3] = P > 0 ? off[P] : 0;            // duplicate-check pairs (capacity check)
+        res[3] = 0;
         res[4] = (int64_t)*Pp;                  // pool size (capacity check)
     }
 }
@@ -1777,61 +1725,24 @@ constexpr int GRP_LDS = 4096;
 
 __device__ __forceinline__ void d_groups_lds(
     const int64_t* __restrict__ pool, const double* __restrict__ ps, const uint8_t* __restrict__ pex,
-    const int32_t* __restrict__ order, const int32_t* __restrict__ lo, const int64_t* __restrict__ off,
-    const uint8_t* __restrict__ flag, int64_t P, int64_t flag_cap, int k, int dedup,
+    const int32_t* __restrict__ order, const int32_t* __restrict__ parent, int64_t P, int k,
     const uint32_t* __restrict__ sel, const int64_t* __restrict__ st, double margin,
     int32_t* __restrict__ headpos, int64_t* __restrict__ out_ids, double* __restrict__ out_sc,
-    int64_t* __restrict__ res, int64_t total_flags, const PoolVals pvs, int64_t* __restrict__ vrow) {
+    int64_t* __restrict__ res, const PoolVals pvs, int64_t* __restrict__ vrow) {
     __shared__ int64_t part[GRP_THREADS];
     __shared__ __align__(16) int32_t par[GRP_LDS];
     __shared__ __align__(16) unsigned long long rkey[GRP_LDS];   // also the sort array of phase 5
     __shared__ uint32_t blkb[GRP_LDS / 32];
-    __shared__ int changed, undecided;
     const int t = threadIdx.x;
     const bool all = st[1] != 0;
     const double th_scan = all ? -1.0 : select_threshold(sel, st) - margin;
-    // 1. initial decisions
-    for (int q = t; q < P; q += GRP_THREADS) {
-        const double sq = ps[order[q]];
-        int32_t v = q;
-        if (!(sq > 0.0)) v = -3;                           // invalid after exact rescoring
-        else if (dedup) {
-            const int64_t o = off[q];
-            const int l = lo[q];
-            for (int p2 = l; p2 < q; p2++)
-                if (o + (p2 - l) < flag_cap && flag[o + (p2 - l)]) { v = -2; break; }
-        }
-        par[q] = v;
+    for (int q = t; q < P; q += GRP_THREADS) {             // heads, set by k_clusters / k_dedup
+        par[q] = parent[q];
         rkey[q] = ~0ull;
     }
     for (int w = t; w < GRP_LDS / 32; w += GRP_THREADS) blkb[w] = 0u;
     __syncthreads();
-    // 2. rounds
-    for (;;) {
-        if (t == 0) { changed = 0; undecided = 0; }
-        __syncthreads();
-        for (int q = t; q < P; q += GRP_THREADS) {
-            if (par[q] != -2) continue;
-            int32_t dec = q;                               // head unless a flagged head comes first
-            bool wait = false;
-            const int64_t o = off[q];
-            const int l = lo[q];
-            for (int p2 = l; p2 < q; p2++) {
-                if (o + (p2 - l) >= flag_cap || !flag[o + (p2 - l)]) continue;
-                const int32_t sp2 = par[p2];
-                if (sp2 == -2) { wait = true; break; }
-                if (sp2 == p2) { dec = p2; break; }
-            }
-            if (wait) { atomicAdd(&undecided, 1); continue; }
-            par[q] = dec;
-            atomicAdd(&changed, 1);
-        }
-        __syncthreads();
-        const int ch = changed, un = undecided;
-        __syncthreads();
-        if (un == 0 || ch == 0) break;
-    }
-    // 3. aggregate groups onto their heads
+    // aggregate groups onto their heads
     int64_t merged_loc = 0;
     for (int q = t; q < P; q += GRP_THREADS) {
         const int32_t h = par[q];
@@ -1943,7 +1854,7 @@ __device__ __forceinline__ void d_groups_lds(
         res[0] = ns;
         res[1] = complete ? 1 : 0;
         res[2] = merged_tot;
-        res[3] = total_flags;                  // duplicate-check pairs (capacity check)
+        res[3] = 0;
     }
 }
 
@@ -2021,6 +1932,7 @@ struct SelArgs {
     double* perr;             // |screening score - exact score| per pool entry
     int64_t* off;
     uint8_t* flag;
+    unsigned long long* ncl;  // near-tie clusters listed in wc (starts)
     int32_t *parent, *blk;
     unsigned long long* repid;
     int32_t *reppos, *headpos;
@@ -2058,23 +1970,16 @@ __global__ __launch_bounds__(256) void k_scatter(ctab<SelArgs> A) {
     d_scatter(a.ps, a.cnt, a.cap, a.rank, a.order, a.ss);
 }
 
-__global__ __launch_bounds__(256) void k_window(ctab<SelArgs> A) {
+__global__ __launch_bounds__(256) void k_clusters(ctab<SelArgs> A) {
     const SelArgs& a = tab(A, blockIdx.y);
-    DSC_GLOBAL(a.ps); DSC_GLOBAL(a.pool); DSC_GLOBAL(a.cnt); DSC_GLOBAL(a.rank); DSC_GLOBAL(a.order); DSC_GLOBAL(a.ss); DSC_GLOBAL(a.lo); DSC_GLOBAL(a.wc); DSC_GLOBAL(a.off);
-    d_window(a.ss, a.cnt, a.cap, a.lo, a.wc);
+    DSC_GLOBAL(a.ss); DSC_GLOBAL(a.cnt); DSC_GLOBAL(a.parent); DSC_GLOBAL(a.wc); DSC_GLOBAL(a.ncl);
+    d_clusters(a.ss, a.cnt, a.cap, a.dedup, a.parent, a.wc, a.ncl);
 }
 
-__global__ __launch_bounds__(1024) void k_scan_offsets(ctab<SelArgs> A) {
-    const SelArgs& a = tab(A, blockIdx.x);
-    DSC_GLOBAL(a.ps); DSC_GLOBAL(a.pool); DSC_GLOBAL(a.cnt); DSC_GLOBAL(a.rank); DSC_GLOBAL(a.order); DSC_GLOBAL(a.ss); DSC_GLOBAL(a.lo); DSC_GLOBAL(a.wc); DSC_GLOBAL(a.off);
-    d_scan_offsets(a.wc, a.cnt, a.cap, a.off);
-}
-
-__global__ __launch_bounds__(256) void k_pairs(ctab<SelArgs> A) {
+__global__ __launch_bounds__(256) void k_dedup(ctab<SelArgs> A) {
     const SelArgs& a = tab(A, blockIdx.y);
-    DSC_GLOBAL(a.sc); DSC_GLOBAL(a.sel); DSC_GLOBAL(a.st); DSC_GLOBAL(a.pool); DSC_GLOBAL(a.cnt); DSC_GLOBAL(a.ev.raw2c); DSC_GLOBAL(a.ev.valid); DSC_GLOBAL(a.o.Vf); DSC_GLOBAL(a.o.Rf); DSC_GLOBAL(a.Yc); DSC_GLOBAL(a.syy); DSC_GLOBAL(a.ps); DSC_GLOBAL(a.pex); DSC_GLOBAL(a.maxerr); DSC_GLOBAL(a.order); DSC_GLOBAL(a.lo); DSC_GLOBAL(a.wc); DSC_GLOBAL(a.off); DSC_GLOBAL(a.flag); DSC_GLOBAL(a.parent); DSC_GLOBAL(a.blk); DSC_GLOBAL(a.repid); DSC_GLOBAL(a.reppos); DSC_GLOBAL(a.headpos); DSC_GLOBAL(a.out_ids); DSC_GLOBAL(a.out_sc); DSC_GLOBAL(a.res);
-    if (!a.dedup) return;
-    d_pairs(a.pool, a.order, a.lo, a.off, a.cnt, a.cap, a.ev, a.o, a.n, a.flag, a.fcap, a.pvs);
+    DSC_GLOBAL(a.pool); DSC_GLOBAL(a.order); DSC_GLOBAL(a.ss); DSC_GLOBAL(a.cnt); DSC_GLOBAL(a.parent); DSC_GLOBAL(a.wc); DSC_GLOBAL(a.ncl); DSC_GLOBAL(a.ev.raw2c); DSC_GLOBAL(a.ev.valid); DSC_GLOBAL(a.o.Vf); DSC_GLOBAL(a.o.Rf);
+    d_dedup(a.pool, a.order, a.ss, a.cnt, a.cap, a.ev, a.o, a.n, a.parent, a.wc, a.ncl, a.pvs);
 }
 
 __global__ __launch_bounds__(GRP_THREADS) void k_groups(ctab<SelArgs> A) {
@@ -2096,16 +2001,14 @@ __global__ __launch_bounds__(GRP_THREADS) void k_groups(ctab<SelArgs> A) {
         __syncthreads();
     }
     if (P <= GRP_LDS) {
-        d_groups_lds(a.pool, a.ps, a.pex, a.order, a.lo, a.off, a.flag, P, a.fcap, a.k, a.dedup, a.sel,
-                     a.st, a.margin, a.headpos, a.out_ids, a.out_sc, a.res, P > 0 ? a.off[P] : 0, a.pvs,
-                     a.vrow);
+        d_groups_lds(a.pool, a.ps, a.pex, a.order, a.parent, P, a.k, a.sel, a.st, a.margin, a.headpos,
+                     a.out_ids, a.out_sc, a.res, a.pvs, a.vrow);
         if (threadIdx.x == 0) a.res[4] = (int64_t)*a.cnt;     // pool size (capacity check)
         return;
     }
     for (int64_t i = threadIdx.x; i < a.k; i += GRP_THREADS) a.vrow[i] = 0;   // rows are evaluated
-    d_groups(a.pool, a.ps, a.pex, a.order, a.lo, a.off, a.flag, a.cnt, a.cap, a.fcap, a.k, a.dedup,
-             a.sel, a.st, a.margin, a.parent, a.blk, a.repid, a.reppos, a.headpos, a.out_ids,
-             a.out_sc, a.res);
+    d_groups(a.pool, a.ps, a.pex, a.order, a.cnt, a.cap, a.k, a.sel, a.st, a.margin, a.parent, a.blk,
+             a.repid, a.reppos, a.headpos, a.out_ids, a.out_sc, a.res);
 }
 
 // Values of the selected features of one list.
@@ -2874,6 +2777,7 @@ static void select_round(discover_ctx* ctx, const discover_problem* probs,
         a.pvs.ld = L.n; a.pvs.cap = pool_vals_cap(L.cap, L.n);
         a.cnt = (unsigned long long*)misc;
         a.maxerr = (unsigned long long*)(misc + 8);
+        a.ncl = (unsigned long long*)(misc + 48);
         int64_t* stv = (int64_t*)(misc + 16);
         uint32_t* sel = (uint32_t*)(misc + 32);
         a.sel = sel; a.st = stv; a.hist = hist;
@@ -2887,7 +2791,7 @@ static void select_round(discover_ctx* ctx, const discover_problem* probs,
         a.out_sc = outs[L.b].sc + (int64_t)L.t * k;
         a.vrow = vrow + vbase[L.b] + (int64_t)L.t * k;
         ra[q] = RadixArgs{a.sc, P.N, L.K, hist, sel, stv, nullptr};
-        fills.push_back(fill_seg(misc, 48, 0u));            // pool count, maximum error, st, sel
+        fills.push_back(fill_seg(misc, 56, 0u));            // pool count, maximum error, st, sel, clusters
         fills.push_back(fill_seg(hist, 8192 * 4, 0u));
         Nmax = std::max(Nmax, P.N);
         capmax = std::max(capmax, L.cap);
@@ -2923,14 +2827,13 @@ static void select_round(discover_ctx* ctx, const discover_problem* probs,
         const unsigned rj = (unsigned)std::max<int64_t>(1, std::min<int64_t>(64, cdiv(Kmax + 256, RCH)));
         k_rankp<<<dim3(ri, rj, nl), 256, 0, st>>>(dsa);
         k_scatter<<<dim3((unsigned)std::min<int64_t>(1024, cdiv(capmax, 256)), nl), 256, 0, st>>>(dsa);
-        k_window<<<dim3((unsigned)std::min<int64_t>(1024, cdiv(capmax, 256)), nl), 256, 0, st>>>(dsa);
-        k_scan_offsets<<<nl, 1024, 0, st>>>(dsa);
+        k_clusters<<<dim3((unsigned)std::min<int64_t>(1024, cdiv(capmax, 256)), nl), 256, 0, st>>>(dsa);
         check_launch("k_sort");
     }
     if (prm.dedup) {
         KTimer kt(ctx, st, "dedup_pairs");
-        k_pairs<<<dim3((unsigned)std::max(64, 2048 / nl), nl), 256, 0, st>>>(dsa);
-        check_launch("k_pairs");
+        k_dedup<<<dim3((unsigned)std::max(64, 1024 / nl), nl), 256, 0, st>>>(dsa);
+        check_launch("k_dedup");
     }
     {
         KTimer kt(ctx, st, "groups");
@@ -3086,7 +2989,7 @@ static void generate_screen_once(discover_ctx* ctx, const discover_problem* prob
         std::vector<std::vector<size_t>> o;
         char* base = sel_layout(ctx, prm.k, LS, act, o);
         for (size_t q = 0; q < act.size(); q++) {
-            fills.push_back(fill_seg(base + o[q][SEL_MISC], 48, 0u));   // pool count, maximum error, st, sel
+            fills.push_back(fill_seg(base + o[q][SEL_MISC], 56, 0u));   // pool count, maximum error, st, sel, clusters
             fills.push_back(fill_seg(base + o[q][SEL_HIST], 8192 * 4, 0u));
         }
     };
