@@ -467,6 +467,7 @@ def large_main(args):
         "ms_per_step_fp64_screening": res["fp64"][0] * 1e3,
         "speedup_bf16_vs_fp64": res["fp64"][0] / dt,
         "identical_selections_bf16_fp64": bool(same),
+        "pool_sizes_bf16": [s["pool_size"] for s in stats],
         "max_lowprec_err": max(s["max_lowprec_err"] for s in stats),
         "guard_band": max(s["guard_band"] for s in stats),
         "kernels_bf16": kern, "kernels_fp64": res["fp64"][2],

@@ -152,6 +152,11 @@ typedef struct {
                                  (default), or 1, 2, 4 operand features per wave
                                  (capped by what the target count allows); the
                                  scores do not depend on it */
+    int32_t lp_pairs;         /* precision forms, pair candidates of rungs <= 2: 0 = the
+                                 MFMA form or the FP64 tiles, whichever the autotuner
+                                 times faster for the shape (default); 1 = always the
+                                 MFMA form; -1 = always FP64.  The selection does not
+                                 depend on it */
 } discover_screen_params;
 
 /* Per-problem counters of one screening call (host memory). */

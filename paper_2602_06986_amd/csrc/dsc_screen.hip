@@ -1468,10 +1468,15 @@ __device__ __forceinline__ void d_scatter(const double* __restrict__ ps,
 // Near-tie clusters of the sorted pool.  Entries q-1 and q are chained when
 // ss[q-1] - ss[q] <= TAU_NEAR ss[q-1]; a cluster is a maximal chain.  A
 // group head h can only take entries of its own cluster: across a break,
-// ss[h] - ss[q] exceeds TAU_NEAR ss[h].  Every valid entry starts as its own
-// head (parent[q] = q; -3 for an entry whose exact score is not positive),
-// and the start of every cluster of two or more entries is listed for
-// k_dedup (count in *ncl).
+// ss[h] - ss[q] exceeds TAU_NEAR ss[h].  Groups are formed over a prefix of
+// the sorted pool: its first K entries, extended to the end of their last
+// cluster (*pdp); entries past it cannot join a group that starts inside
+// it, and the group pass checks that none of them could be selected.  (The
+// pool of a precision form holds the whole guard band, most of which
+// scores below the k-th group once rescored.)  Every valid entry of the
+// prefix starts as its own head (parent[q] = q); entries whose exact score
+// is not positive, and entries past the prefix, get -3.  The start of every
+// cluster of two or more entries is listed for k_dedup (count in *ncl).
 __device__ __forceinline__ bool chained(const double* __restrict__ ss, int64_t q) {
     const double sp = ss[q - 1], s = ss[q];
     return s > 0.0 && sp - s <= TAU_NEAR * sp;
@@ -1479,15 +1484,25 @@ __device__ __forceinline__ bool chained(const double* __restrict__ ss, int64_t q
 
 __device__ __forceinline__ void d_clusters(const double* __restrict__ ss,
                                            const unsigned long long* __restrict__ Pp, int64_t cap,
-                                           int dedup, int32_t* __restrict__ parent,
+                                           int64_t K, int dedup, int32_t* __restrict__ parent,
                                            int32_t* __restrict__ starts,
-                                           unsigned long long* __restrict__ ncl) {
+                                           unsigned long long* __restrict__ ncl,
+                                           unsigned long long* __restrict__ pdp) {
+    __shared__ int64_t s_pd;
     const int64_t P = min((int64_t)*Pp, cap);
+    if (threadIdx.x == 0) {
+        int64_t q = min(K, P);
+        while (q > 0 && q < P && chained(ss, q)) q++;
+        s_pd = q;
+        if (blockIdx.x == 0) *pdp = (unsigned long long)q;
+    }
+    __syncthreads();
+    const int64_t Pd = s_pd;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < P;
          q += (int64_t)gridDim.x * blockDim.x) {
-        const bool valid = ss[q] > 0.0;
+        const bool valid = q < Pd && ss[q] > 0.0;
         parent[q] = valid ? (int32_t)q : -3;
-        if (dedup && valid && (q == 0 || !chained(ss, q)) && q + 1 < P && chained(ss, q + 1))
+        if (dedup && valid && (q == 0 || !chained(ss, q)) && q + 1 < Pd && chained(ss, q + 1))
             starts[atomicAdd(ncl, 1ull)] = (int32_t)q;
     }
 }
@@ -1536,7 +1551,13 @@ __device__ __forceinline__ bool dup_pair(const int64_t* __restrict__ pool, int32
 // that is still free and is its duplicate.  So each entry joins the
 // earliest head in its window of which it is a duplicate, and heads only
 // are compared: a group of G equal scores costs G - 1 correlations, not a
-// window of pairs.
+// window of pairs.  The head's centred values are staged in LDS once (from
+// its stored row, or evaluated); a member is read from its stored row, or
+// evaluated once into registers (n <= 2048), so |corr| is formed with the
+// same two-pass products as for two stored rows.
+constexpr int DEDUP_LDS_N = 4096;     // longest head row staged in LDS
+constexpr int DEDUP_REG = 32;         // member values per lane held in registers
+
 __device__ __forceinline__ void d_dedup(const int64_t* __restrict__ pool, const int32_t* __restrict__ order,
                                         const double* __restrict__ ss,
                                         const unsigned long long* __restrict__ Pp, int64_t cap,
@@ -1544,10 +1565,16 @@ __device__ __forceinline__ void d_dedup(const int64_t* __restrict__ pool, const 
                                         const int32_t* __restrict__ starts,
                                         const unsigned long long* __restrict__ ncl, const PoolVals& pvs) {
     __shared__ int64_t s_head, s_end, s_c1;
+    __shared__ double s_huu;
+    __shared__ int s_hok;
+    __shared__ double hc[DEDUP_LDS_N];
     const int64_t P = min((int64_t)*Pp, cap);
     const int64_t nc = (int64_t)*ncl;
     const int w = wave_id(), nw = blockDim.x / 64;
+    const int lane = threadIdx.x & 63;
+    const bool staged = n <= DEDUP_LDS_N;
     volatile int32_t* vpar = parent;
+    auto stored = [&](int32_t i) { return i < pvs.cap && !isnan(pvs.sxx[i]); };
     for (int64_t c = blockIdx.x; c < nc; c += gridDim.x) {
         if (threadIdx.x == 0) {
             const int64_t c0 = starts[c];
@@ -1561,6 +1588,7 @@ __device__ __forceinline__ void d_dedup(const int64_t* __restrict__ pool, const 
         for (;;) {
             const int64_t h = s_head;
             if (h >= c1) break;
+            const int32_t ih = order[h];
             if (threadIdx.x == 0) {              // the head's window: a prefix of (h, c1)
                 const double sh = ss[h];
                 int64_t lo = h, hi = c1;         // in window up to lo, not from hi
@@ -1570,13 +1598,94 @@ __device__ __forceinline__ void d_dedup(const int64_t* __restrict__ pool, const 
                 }
                 s_end = lo + 1;
             }
+            if (staged && w == 0) {              // head row, centred, into LDS
+                if (stored(ih)) {
+                    const double* u = pvs.v + (int64_t)ih * pvs.ld;
+                    const double mu_ = pvs.mean[ih];
+                    for (int i = lane; i < n; i += 64) hc[i] = u[i] - mu_;
+                    if (lane == 0) { s_huu = pvs.sxx[ih]; s_hok = 1; }
+                } else {
+                    Cand ch;
+                    const bool ok = cand_of_id(ev, pool[ih], ch);
+                    double su = 0.0;
+                    if (ok)
+                        for (int i = lane; i < n; i += 64) {
+                            const double x = cand_value(ch, o, i);
+                            hc[i] = x;
+                            su += x;
+                        }
+                    const double mu_ = wave_sum(su) / n;
+                    double uu = 0.0;
+                    if (ok)
+                        for (int i = lane; i < n; i += 64) {
+                            const double d = hc[i] - mu_;
+                            hc[i] = d;
+                            uu += d * d;
+                        }
+                    uu = wave_sum(uu);
+                    if (lane == 0) { s_huu = uu; s_hok = ok ? 1 : 0; }
+                }
+            }
             __syncthreads();
             const int64_t e = s_end;
-            const int32_t ih = order[h];
             for (int64_t q = h + 1 + w; q < e; q += nw) {
                 if (vpar[q] != (int32_t)q) continue;          // taken by an earlier head
-                if (dup_pair(pool, ih, order[q], ev, o, n, pvs) && (threadIdx.x & 63) == 0)
-                    vpar[q] = (int32_t)h;
+                const int32_t iv = order[q];
+                bool dup;
+                if (!staged) {
+                    dup = dup_pair(pool, ih, iv, ev, o, n, pvs);
+                } else if (!s_hok) {
+                    dup = false;
+                } else if (stored(iv)) {
+                    const double* v = pvs.v + (int64_t)iv * pvs.ld;
+                    const double mv = pvs.mean[iv];
+                    double uv = 0.0;
+                    for (int i = lane; i < n; i += 64) uv += hc[i] * (v[i] - mv);
+                    uv = wave_sum(uv);
+                    dup = fabs(uv) / sqrt(s_huu * pvs.sxx[iv]) >= 1.0 - TAU_DUP;
+                } else {
+                    Cand cv;
+                    if (!cand_of_id(ev, pool[iv], cv)) {
+                        dup = false;
+                    } else if (n <= 64 * DEDUP_REG) {
+                        double rv[DEDUP_REG];
+                        double sv = 0.0;
+#pragma unroll
+                        for (int j = 0; j < DEDUP_REG; j++) {
+                            const int i = lane + 64 * j;
+                            rv[j] = i < n ? cand_value(cv, o, i) : 0.0;
+                            sv += rv[j];
+                        }
+                        const double mv = wave_sum(sv) / n;
+                        double vv = 0.0, uv = 0.0;
+#pragma unroll
+                        for (int j = 0; j < DEDUP_REG; j++) {
+                            const int i = lane + 64 * j;
+                            if (i < n) {
+                                const double dv = rv[j] - mv;
+                                vv += dv * dv;
+                                uv += hc[i] * dv;
+                            }
+                        }
+                        vv = wave_sum(vv);
+                        uv = wave_sum(uv);
+                        dup = fabs(uv) / sqrt(s_huu * vv) >= 1.0 - TAU_DUP;
+                    } else {
+                        double sv = 0.0;
+                        for (int i = lane; i < n; i += 64) sv += cand_value(cv, o, i);
+                        const double mv = wave_sum(sv) / n;
+                        double vv = 0.0, uv = 0.0;
+                        for (int i = lane; i < n; i += 64) {
+                            const double dv = cand_value(cv, o, i) - mv;
+                            vv += dv * dv;
+                            uv += hc[i] * dv;
+                        }
+                        vv = wave_sum(vv);
+                        uv = wave_sum(uv);
+                        dup = fabs(uv) / sqrt(s_huu * vv) >= 1.0 - TAU_DUP;
+                    }
+                }
+                if (dup && lane == 0) vpar[q] = (int32_t)h;
             }
             __threadfence_block();
             __syncthreads();
@@ -1620,7 +1729,7 @@ __device__ __forceinline__ int64_t block_excl_scan(int64_t v, int64_t* part) {
 __device__ __forceinline__ void d_groups(
     const int64_t* __restrict__ pool, const double* __restrict__ ps, const uint8_t* __restrict__ pex,
     const int32_t* __restrict__ order, const unsigned long long* __restrict__ Pp, int64_t cap,
-    int k, const uint32_t* __restrict__ sel,
+    double tail, int k, const uint32_t* __restrict__ sel,
     const int64_t* __restrict__ st, double margin, int32_t* __restrict__ parent,
     int32_t* __restrict__ blk, unsigned long long* __restrict__ repid, int32_t* __restrict__ reppos,
     int32_t* __restrict__ headpos, int64_t* __restrict__ out_ids, double* __restrict__ out_sc,
@@ -1703,10 +1812,13 @@ __device__ __forceinline__ void d_groups(
         out_sc[i] = __longlong_as_double(0x7FF8000000000000LL);
     }
     if (t == 0) {
-        bool complete = all;
-        if (!all && nunb >= k) {
+        // the scan reached below the near-tie window of the k-th unblocked
+        // head, both in the pool and in the grouped prefix (tail: the first
+        // score past it)
+        bool complete = all && !(tail > 0.0);
+        if (nunb >= k) {
             const double lim = ps[order[headpos[k - 1]]];
-            complete = (1.0 - TAU_NEAR) * lim >= th_scan;
+            complete = (all || (1.0 - TAU_NEAR) * lim >= th_scan) && (1.0 - TAU_NEAR) * lim > tail;
         }
         res[0] = ns;
         res[1] = complete ? 1 : 0;
@@ -1725,7 +1837,7 @@ constexpr int GRP_LDS = 4096;
 
 __device__ __forceinline__ void d_groups_lds(
     const int64_t* __restrict__ pool, const double* __restrict__ ps, const uint8_t* __restrict__ pex,
-    const int32_t* __restrict__ order, const int32_t* __restrict__ parent, int64_t P, int k,
+    const int32_t* __restrict__ order, const int32_t* __restrict__ parent, int64_t P, double tail, int k,
     const uint32_t* __restrict__ sel, const int64_t* __restrict__ st, double margin,
     int32_t* __restrict__ headpos, int64_t* __restrict__ out_ids, double* __restrict__ out_sc,
     int64_t* __restrict__ res, const PoolVals pvs, int64_t* __restrict__ vrow) {
@@ -1846,10 +1958,13 @@ __device__ __forceinline__ void d_groups_lds(
         out_sc[i] = __longlong_as_double(0x7FF8000000000000LL);
     }
     if (t == 0) {
-        bool complete = all;
-        if (!all && nunb >= k) {
+        // the scan reached below the near-tie window of the k-th unblocked
+        // head, both in the pool and in the grouped prefix (tail: the first
+        // score past it)
+        bool complete = all && !(tail > 0.0);
+        if (nunb >= k) {
             const double lim = ps[order[headpos[k - 1]]];
-            complete = (1.0 - TAU_NEAR) * lim >= th_scan;
+            complete = (all || (1.0 - TAU_NEAR) * lim >= th_scan) && (1.0 - TAU_NEAR) * lim > tail;
         }
         res[0] = ns;
         res[1] = complete ? 1 : 0;
@@ -1933,6 +2048,7 @@ struct SelArgs {
     int64_t* off;
     uint8_t* flag;
     unsigned long long* ncl;  // near-tie clusters listed in wc (starts)
+    unsigned long long* pd;   // end of the grouped prefix of the sorted pool
     int32_t *parent, *blk;
     unsigned long long* repid;
     int32_t *reppos, *headpos;
@@ -1972,11 +2088,13 @@ __global__ __launch_bounds__(256) void k_scatter(ctab<SelArgs> A) {
 
 __global__ __launch_bounds__(256) void k_clusters(ctab<SelArgs> A) {
     const SelArgs& a = tab(A, blockIdx.y);
-    DSC_GLOBAL(a.ss); DSC_GLOBAL(a.cnt); DSC_GLOBAL(a.parent); DSC_GLOBAL(a.wc); DSC_GLOBAL(a.ncl);
-    d_clusters(a.ss, a.cnt, a.cap, a.dedup, a.parent, a.wc, a.ncl);
+    DSC_GLOBAL(a.ss); DSC_GLOBAL(a.cnt); DSC_GLOBAL(a.parent); DSC_GLOBAL(a.wc); DSC_GLOBAL(a.ncl); DSC_GLOBAL(a.pd);
+    d_clusters(a.ss, a.cnt, a.cap, a.K, a.dedup, a.parent, a.wc, a.ncl, a.pd);
 }
 
-__global__ __launch_bounds__(256) void k_dedup(ctab<SelArgs> A) {
+constexpr int DEDUP_THREADS = 512;
+
+__global__ __launch_bounds__(DEDUP_THREADS) void k_dedup(ctab<SelArgs> A) {
     const SelArgs& a = tab(A, blockIdx.y);
     DSC_GLOBAL(a.pool); DSC_GLOBAL(a.order); DSC_GLOBAL(a.ss); DSC_GLOBAL(a.cnt); DSC_GLOBAL(a.parent); DSC_GLOBAL(a.wc); DSC_GLOBAL(a.ncl); DSC_GLOBAL(a.ev.raw2c); DSC_GLOBAL(a.ev.valid); DSC_GLOBAL(a.o.Vf); DSC_GLOBAL(a.o.Rf);
     d_dedup(a.pool, a.order, a.ss, a.cnt, a.cap, a.ev, a.o, a.n, a.parent, a.wc, a.ncl, a.pvs);
@@ -2000,14 +2118,17 @@ __global__ __launch_bounds__(GRP_THREADS) void k_groups(ctab<SelArgs> A) {
         }
         __syncthreads();
     }
-    if (P <= GRP_LDS) {
-        d_groups_lds(a.pool, a.ps, a.pex, a.order, a.parent, P, a.k, a.sel, a.st, a.margin, a.headpos,
-                     a.out_ids, a.out_sc, a.res, a.pvs, a.vrow);
+    // groups live in the prefix [0, Pd) of the sorted pool
+    const int64_t Pd = min((int64_t)*a.pd, P);
+    const double tail = Pd < P ? a.ps[a.order[Pd]] : -1.0;
+    if (Pd <= GRP_LDS) {
+        d_groups_lds(a.pool, a.ps, a.pex, a.order, a.parent, Pd, tail, a.k, a.sel, a.st, a.margin,
+                     a.headpos, a.out_ids, a.out_sc, a.res, a.pvs, a.vrow);
         if (threadIdx.x == 0) a.res[4] = (int64_t)*a.cnt;     // pool size (capacity check)
         return;
     }
     for (int64_t i = threadIdx.x; i < a.k; i += GRP_THREADS) a.vrow[i] = 0;   // rows are evaluated
-    d_groups(a.pool, a.ps, a.pex, a.order, a.cnt, a.cap, a.k, a.sel, a.st, a.margin, a.parent, a.blk,
+    d_groups(a.pool, a.ps, a.pex, a.order, a.cnt, a.cap, tail, a.k, a.sel, a.st, a.margin, a.parent, a.blk,
              a.repid, a.reppos, a.headpos, a.out_ids, a.out_sc, a.res);
 }
 
@@ -2448,6 +2569,39 @@ static int tune_dense(discover_ctx* ctx, const std::string& key, int cls, int TP
     return bestJ;
 }
 
+// Autotuned choice of the precision form for one problem's dense pair
+// tiles: the MFMA kernel and the FP64 tiles (one operand feature per wave)
+// are each timed once for this shape, their counter bumps undone, and the
+// faster is remembered.  (Both give the same selection: the FP64 scores lie
+// within the guard band of their own exact values.)
+static bool tune_precision(discover_ctx* ctx, const std::string& key, Problem& P,
+                           const std::function<void()>& run_lp, ctab<PairArgs> dA, int b, hipStream_t st) {
+    auto it = ctx->tuned.find(key);
+    if (it != ctx->tuned.end()) return it->second != 0;
+    if (ctx->capturing) DSC_FAIL(DISCOVER_E_CAPACITY, "precision-form tuning during graph capture");
+    unsigned long long* sv = ctx->buf<unsigned long long>("tune_lp_ctr", 4);
+    DSC_HIP(hipMemcpyAsync(sv, P.ctr, 32, hipMemcpyDeviceToDevice, st));
+    std::vector<int4> tiles;
+    for (const int2& t : P.plan->dtilesJ[0]) tiles.push_back(make_int4(b, t.x, t.y, 0));
+    const int4* dt = ctx->upload("tune_lp_tiles", tiles, st);
+    float ms[2] = {0.f, 0.f};
+    for (int v = 0; v < 2; v++) {
+        hipEvent_t e0 = ctx->event(), e1 = ctx->event();
+        DSC_HIP(hipEventRecord(e0, st));
+        if (v == 0) run_lp();
+        else launch_pairs(P.plan->dense_cls, dA, dt, (int64_t)tiles.size(), false, P.TP, 1, st);
+        DSC_HIP(hipEventRecord(e1, st));
+        DSC_HIP(hipMemcpyAsync(P.ctr, sv, 32, hipMemcpyDeviceToDevice, st));
+        DSC_HIP(hipEventSynchronize(e1));
+        DSC_HIP(hipEventElapsedTime(&ms[v], e0, e1));
+        ctx->free_events.push_back(e0);
+        ctx->free_events.push_back(e1);
+    }
+    const bool lp = ms[0] < ms[1];
+    ctx->tuned[key] = lp ? 1 : 0;
+    return lp;
+}
+
 // Materialise the operand features of every problem and screen every
 // candidate into its score slots (no host synchronisation).
 static void screen_all(discover_ctx* ctx, const discover_problem* probs, int nb,
@@ -2578,7 +2732,10 @@ static void screen_all(discover_ctx* ctx, const discover_problem* probs, int nb,
     }
     const ctab<PairArgs> dpa = ct(ctx->upload("scr_pairs", pa, st));
     const std::vector<int> order = by_weight(PS);
-    // 6a. precision form: per problem, MFMA screening with FP64 guard-band rescore
+    // 6a. precision form: per problem, MFMA screening with FP64 guard-band
+    // rescore, where the autotuner found it faster than the FP64 tiles for
+    // this problem's shape (either gives the same selection)
+    std::vector<char> lp_used(nb, 0);
     for (int b = 0; b < nb; b++) {
         Problem& P = PS[b];
         const Plan& pl = *P.plan;
@@ -2589,17 +2746,25 @@ static void screen_all(discover_ctx* ctx, const discover_problem* probs, int nb,
         else k_targets_lp<false><<<gy, 256, 0, st>>>(P.n, P.T, P.ldn, P.ldl, P.Yn, (__bf16*)P.ylp);
         PairArgs a = pa[b];
         a.tiles = pl.ptiles; a.n_tiles = pl.n_ptiles;
-        KTimer kt(ctx, st, "screen_lp");
         const double dl = lowprec_delta(prm.precision, P.n);
-        if (fp16) launch_lp<true>(pl.dense_cls, a, P.ylp, P.ldl, dl, st);
-        else launch_lp<false>(pl.dense_cls, a, P.ylp, P.ldl, dl, st);
-        check_launch("k_screen_lp");
+        auto run_lp = [&] {
+            if (fp16) launch_lp<true>(pl.dense_cls, a, P.ylp, P.ldl, dl, st);
+            else launch_lp<false>(pl.dense_cls, a, P.ylp, P.ldl, dl, st);
+            check_launch("k_screen_lp");
+        };
+        if (prm.lp_pairs < 0 ||
+            (prm.lp_pairs == 0 &&
+             !tune_precision(ctx, "lp" + pl.key + std::to_string(P.n) + (fp16 ? "h" : "b"), P, run_lp, dpa, b, st)))
+            continue;                            // FP64 tiles below
+        lp_used[b] = 1;
+        KTimer kt(ctx, st, "screen_lp");
+        run_lp();
     }
     // 6b. FP64 dense tiles, merged per (operator class, padded targets)
     std::map<std::pair<int, int>, std::vector<int>> groups;
     for (int b : order) {
         const Problem& P = PS[b];
-        if (P.pairs && P.plan->dense_ops && prm.precision == DISCOVER_FP64)
+        if (P.pairs && P.plan->dense_ops && !lp_used[b])
             groups[{P.plan->dense_cls, P.TP}].push_back(b);
     }
     int gi = 0;
@@ -2778,6 +2943,7 @@ static void select_round(discover_ctx* ctx, const discover_problem* probs,
         a.cnt = (unsigned long long*)misc;
         a.maxerr = (unsigned long long*)(misc + 8);
         a.ncl = (unsigned long long*)(misc + 48);
+        a.pd = (unsigned long long*)(misc + 56);
         int64_t* stv = (int64_t*)(misc + 16);
         uint32_t* sel = (uint32_t*)(misc + 32);
         a.sel = sel; a.st = stv; a.hist = hist;
@@ -2791,7 +2957,7 @@ static void select_round(discover_ctx* ctx, const discover_problem* probs,
         a.out_sc = outs[L.b].sc + (int64_t)L.t * k;
         a.vrow = vrow + vbase[L.b] + (int64_t)L.t * k;
         ra[q] = RadixArgs{a.sc, P.N, L.K, hist, sel, stv, nullptr};
-        fills.push_back(fill_seg(misc, 56, 0u));            // pool count, maximum error, st, sel, clusters
+        fills.push_back(fill_seg(misc, 64, 0u));            // pool count, maximum error, st, sel, clusters, prefix
         fills.push_back(fill_seg(hist, 8192 * 4, 0u));
         Nmax = std::max(Nmax, P.N);
         capmax = std::max(capmax, L.cap);
@@ -2832,7 +2998,7 @@ static void select_round(discover_ctx* ctx, const discover_problem* probs,
     }
     if (prm.dedup) {
         KTimer kt(ctx, st, "dedup_pairs");
-        k_dedup<<<dim3((unsigned)std::max(64, 1024 / nl), nl), 256, 0, st>>>(dsa);
+        k_dedup<<<dim3((unsigned)std::max(64, 1024 / nl), nl), DEDUP_THREADS, 0, st>>>(dsa);
         check_launch("k_dedup");
     }
     {
@@ -2872,6 +3038,7 @@ static void validate(const discover_problem* probs, int32_t nb, const discover_s
     DSC_REQUIRE(prm->precision >= DISCOVER_FP64 && prm->precision <= DISCOVER_FP16_GUARD,
                 "precision %d", prm->precision);
     DSC_REQUIRE(prm->tile_j >= 0 && prm->tile_j <= 4, "tile_j %d outside 0..4", prm->tile_j);
+    DSC_REQUIRE(prm->lp_pairs >= -1 && prm->lp_pairs <= 1, "lp_pairs %d outside -1..1", prm->lp_pairs);
     for (int r = 1; r <= prm->rung; r++) {
         DSC_REQUIRE((prm->rung_ops[r] & ~DISCOVER_OPS_ALL) == 0, "unknown operator bits at rung %d", r);
         DSC_REQUIRE(prm->rung_pool[r] >= -1 && prm->rung_pool[r] < r, "rung_pool[%d]", r);
@@ -2989,7 +3156,7 @@ static void generate_screen_once(discover_ctx* ctx, const discover_problem* prob
         std::vector<std::vector<size_t>> o;
         char* base = sel_layout(ctx, prm.k, LS, act, o);
         for (size_t q = 0; q < act.size(); q++) {
-            fills.push_back(fill_seg(base + o[q][SEL_MISC], 56, 0u));   // pool count, maximum error, st, sel, clusters
+            fills.push_back(fill_seg(base + o[q][SEL_MISC], 64, 0u));   // pool count, maximum error, st, sel, clusters, prefix
             fills.push_back(fill_seg(base + o[q][SEL_HIST], 8192 * 4, 0u));
         }
     };

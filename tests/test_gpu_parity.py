@@ -321,6 +321,7 @@ def test_precision_multitarget(torch, ctx, D, oracle_mod, prec):
     lists, status, nvalid = O.sis(sp, w["X"], None, w["Y"], w["k"], (), "per_target")
     q = prm_of(D, w, mode="per_target")
     q.precision = D.BF16_GUARD if prec == "bf16" else D.FP16_GUARD
+    q.lp_pairs = 1                                  # the MFMA form, whatever the autotuner prefers
     ids, sc, _, st = ctx.generate_screen(dev(torch, w["X"]), dev(torch, w["Y"]), q)
     for t in range(16):
         check_selection(ids[t].cpu().numpy(), sc[t].cpu().numpy(), lists[t][0], lists[t][1],
@@ -346,11 +347,31 @@ def test_precision_max_mode(torch, ctx, D, oracle_mod, prec, T, B, rung):
     sp = O.Space(p, rung, O.OPS)
     (lst,), status, nvalid = O.sis(sp, X, units, Y, 60, (), "max")
     q = D.params(rung=rung, k=60, score_mode=D.SCORE_MAX,
-                 precision=D.BF16_GUARD if prec == "bf16" else D.FP16_GUARD)
+                 precision=D.BF16_GUARD if prec == "bf16" else D.FP16_GUARD, lp_pairs=1)
     ids, sc, _, st = ctx.generate_screen(dev(torch, X), dev(torch, Y), q, units=units)
     check_selection(ids[0].cpu().numpy(), sc[0].cpu().numpy(), lst[0], lst[1], what="max %s" % prec)
     assert st["n_scored"] == nvalid
     assert st["max_lowprec_err"] <= st["guard_band"]
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_precision_choice_invariant(torch, ctx, D, prec):
+    """The precision form of the pair tiles, the FP64 tiles and the
+    autotuner's choice between them select the same features with the same
+    exact scores and values."""
+    rng = np.random.default_rng(91)
+    p, n, T = 7, 311, 8
+    X = rng.lognormal(0, 0.4, size=(p, n))
+    Y = np.array([X[t % p] / X[(t + 2) % p] + rng.normal(size=n) * 0.3 for t in range(T)])
+    out = []
+    for lp in (1, -1, 0):
+        q = D.params(rung=2, k=40, score_mode=D.SCORE_MAX, lp_pairs=lp,
+                     precision=D.BF16_GUARD if prec == "bf16" else D.FP16_GUARD)
+        out.append(ctx.generate_screen(dev(torch, X), dev(torch, Y), q))
+    for ids, sc, vals, st in out[1:]:
+        assert np.array_equal(ids.cpu().numpy(), out[0][0].cpu().numpy())
+        assert np.array_equal(sc.cpu().numpy(), out[0][1].cpu().numpy())
+        assert np.array_equal(vals.cpu().numpy(), out[0][2].cpu().numpy())
 
 
 # ------------------------------------------------------- operator-limited rung 3
