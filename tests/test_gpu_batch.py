@@ -115,30 +115,6 @@ def test_batch_l0_equals_single(torch, ctx, D, Dd, m):
         assert st["n_subsets"] == bst["n_subsets"]
 
 
-def test_batch128_sisso_vs_oracle(torch, ctx, D, oracle_mod):
-    """The batched loop on four datasets of the 128-dataset workload (the
-    smallest p, every n) against the oracle: identical selections and L0
-    winners, RMSE within the parity bar."""
-    import synth
-    O = oracle_mod
-    ws = synth.batch128()
-    pick = sorted(range(len(ws)), key=lambda b: (ws[b]["X"].shape[0], ws[b]["X"].shape[1]))[:4]
-    sel = [ws[b] for b in pick]
-    Xs = [dev(torch, w["X"]) for w in sel]
-    ys = [dev(torch, w["Y"][0]) for w in sel]
-    prm = D.params(ops=sel[0]["ops"], rung=2, k=sel[0]["k"])
-    got = ctx.sisso_batch(Xs, ys, prm, sel[0]["D"])
-    for w, g in zip(sel, got):
-        ref = O.sisso(w)
-        S_g = g["S_ids"].cpu().numpy()
-        for rd, gd in zip(ref["dims"], g["dims"]):
-            assert set(gd["sel_ids"].cpu().numpy().tolist()) == set(rd["sel_ids"].tolist()), w["name"]
-            win = sorted(int(S_g[i]) for i in gd["subsets"][0].cpu().numpy())
-            assert win == sorted(rd["models"][0]["ids"]), w["name"]
-            r_ref = rd["models"][0]["rmse"]
-            assert abs(float(gd["rmse"][0]) - r_ref) <= 1e-10 * r_ref + 1e-13 * np.std(w["Y"][0])
-
-
 def test_sisso_batch_graph_replays_match_eager(torch, ctx, D):
     """discover_sisso_batch: the eager first call, then several replays of
     its captured graph (with other GPU work and synchronisations between

@@ -113,3 +113,55 @@ def test_sisso_against_reference(torch, ctx, name, prec):
         assert np.max(np.abs(coef - np.array(om["coef"]))) <= 1e-10 * scale
         rmse = float(got["omp"]["rmse"].cpu().numpy().reshape(-1)[0])
         assert abs(rmse - om["rmse"]) <= 1e-10 * om["rmse"] + 1e-13 * np.std(y)
+
+
+def _compare_dataset(name, gold, sel, models, counts, y):
+    """sel[d] = (ids, scores); models[d][q] = (candidate IDs, rmse, coef with
+    the intercept first and the rest in the models' row order)."""
+    for d, rd in enumerate(gold["dims"]):
+        what = "%s dim %d" % (name, d + 1)
+        check_selection(sel[d][0], sel[d][1], rd["sel_ids"], rd["sel_scores"], what=what)
+        if counts is not None:
+            assert counts[d] == (rd["n_valid"], rd["n_unit_valid"]), (what, counts[d])
+        for q, mo in enumerate(rd["models"]):
+            ids_g, rmse_g, coef_g = models[d][q]
+            check_model(ids_g, rmse_g, coef_g, mo, y, "%s model %d" % (what, q))
+
+
+def test_batch128_against_reference(torch, ctx):
+    """All 128 datasets of the batched workload (n ~ U{50..2000}, p ~
+    U{6..20}, rung 2, top-200, D <= 3), through the batched per-dimension
+    calls and through the captured loop (its first call eager, the second a
+    graph replay), against the stored oracle reference of every dataset."""
+    import paper_2602_06986_amd as D
+    path = os.path.join(GOLDEN, "batch128.json")
+    assert os.path.exists(path), "tests/golden/batch128.json is missing"
+    with open(path) as f:
+        gold = json.load(f)["datasets"]
+    ws = synth.batch128()
+    assert len(gold) == len(ws) == 128
+    for w, g in zip(ws, gold):
+        assert fingerprint(w) == g["fingerprint"], w["name"]
+    Xs = [torch.as_tensor(w["X"], device="cuda") for w in ws]
+    ys = [torch.as_tensor(w["Y"][0], device="cuda").contiguous() for w in ws]
+    prm = D.params(ops=ws[0]["ops"], rung=2, k=ws[0]["k"])
+    Dd = ws[0]["D"]
+    loop = ctx.sisso_batch(Xs, ys, prm, Dd)
+    for b, (w, g, r) in enumerate(zip(ws, gold, loop)):
+        S = r["S_ids"].cpu().numpy()
+        assert [int(v) for v in S] == g["S_ids"], w["name"]
+        sel = [(dd["sel_ids"].cpu().numpy(), dd["sel_scores"].cpu().numpy()) for dd in r["dims"]]
+        models = [[([int(S[i]) for i in dd["subsets"][q].cpu().numpy()], float(dd["rmse"][q]),
+                    dd["coef"][q].cpu().numpy()) for q in range(len(dd["rmse"]))] for dd in r["dims"]]
+        counts = [(dd["screen_stats"]["n_scored"], dd["screen_stats"]["n_unit_valid"]) for dd in r["dims"]]
+        _compare_dataset(w["name"] + " (batched calls)", g, sel, models, counts, w["Y"][0])
+    for call in range(2):
+        ids, sc, sub, rmse, coef, rep = ctx.sisso_batch_graph(Xs, ys, prm, Dd, m=1)
+        assert rep == (1 if call else 0), (call, rep)
+        ids, sc, sub, rmse, coef = (t.cpu().numpy() for t in (ids, sc, sub, rmse, coef))
+        for b, (w, g) in enumerate(zip(ws, gold)):
+            S = ids[b].reshape(-1)
+            sel = [(ids[b, d], sc[b, d]) for d in range(Dd)]
+            models = [[([int(S[i]) for i in sub[b, d, 0, :d + 1]], float(rmse[b, d, 0]),
+                        coef[b, d, 0, :d + 2])] for d in range(Dd)]
+            _compare_dataset("%s (graph call %d)" % (w["name"], call), g, sel, models, None, w["Y"][0])
