@@ -157,6 +157,10 @@ typedef struct {
                                  times faster for the shape (default); 1 = always the
                                  MFMA form; -1 = always FP64.  The selection does not
                                  depend on it */
+    int32_t sched;            /* FP64 dense pair tiles: 0 = autotuned (default), 1 = one
+                                 persistent launch whose blocks take tiles from a device
+                                 work queue (heaviest first), -1 = one block per tile.
+                                 The scores do not depend on it */
 } discover_screen_params;
 
 /* Per-problem counters of one screening call (host memory). */

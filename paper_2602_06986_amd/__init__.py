@@ -39,7 +39,7 @@ class ScreenParams(C.Structure):
     _fields_ = [("ops", C.c_uint32), ("rung", C.c_int32), ("rung_ops", C.c_uint32 * 4),
                 ("rung_pool", C.c_int32 * 4), ("k", C.c_int32), ("score_mode", C.c_int32),
                 ("precision", C.c_int32), ("dedup", C.c_int32), ("tile_j", C.c_int32),
-                ("lp_pairs", C.c_int32)]
+                ("lp_pairs", C.c_int32), ("sched", C.c_int32)]
 
 
 class ScreenStats(C.Structure):
@@ -119,7 +119,7 @@ def _check(code):
 
 
 def params(ops=OPS, rung=1, k=20, score_mode=SCORE_PER_TARGET, precision=FP64, dedup=True,
-           rung_ops=None, rung_pool=None, tile_j=0, lp_pairs=0):
+           rung_ops=None, rung_pool=None, tile_j=0, lp_pairs=0, sched=0):
     """Build the screening parameter struct from operator names."""
     prm = ScreenParams()
     prm.ops = sum(OP_BIT[o] for o in ops)
@@ -135,6 +135,7 @@ def params(ops=OPS, rung=1, k=20, score_mode=SCORE_PER_TARGET, precision=FP64, d
     prm.dedup = 1 if dedup else 0
     prm.tile_j = tile_j
     prm.lp_pairs = lp_pairs
+    prm.sched = sched
     return prm
 
 

@@ -198,8 +198,8 @@ extern "C" discover_status discover_sisso_batch(discover_ctx* ctx, const discove
                     "OMP outputs required");
         DSC_REQUIRE(omp_D == 0 || (int64_t)D * prm->k >= omp_D, "omp_D exceeds the subspace");
         DSC_REQUIRE(prm->rung >= 0 && prm->rung <= DISCOVER_MAX_RUNG && prm->k >= 1, "rung/k");
-        DSC_REQUIRE(prm->tile_j >= 0 && prm->tile_j <= 4 && prm->lp_pairs >= -1 && prm->lp_pairs <= 1,
-                    "tile_j / lp_pairs");
+        DSC_REQUIRE(prm->tile_j >= 0 && prm->tile_j <= 4 && prm->lp_pairs >= -1 && prm->lp_pairs <= 1 &&
+                    prm->sched >= -1 && prm->sched <= 1, "tile_j / lp_pairs / sched");
         DSC_REQUIRE(prm->score_mode == DISCOVER_SCORE_PER_TARGET, "the first dimension screens one target");
         int nmax = 0;
         for (int b = 0; b < n_problems; b++) {

@@ -531,16 +531,16 @@ constexpr int pair_split() { return LIST ? 8 : 4; }
 // Tiles of every problem of a call form one list, heaviest first:
 // (problem, jc0, ic0, -) dense or (problem, jc, list offset, count) in list
 // mode; the problem's arguments are read from A.
+constexpr int PAIR_SL = 8;                       // accumulators combined per LDS round
+
 template <int OPS, int J, int TP, bool LIST>
-__global__ __launch_bounds__(64 * pair_split<LIST>()) void k_screen_pairs(ctab<PairArgs> A,
-                                                      const int4* __restrict__ tiles) {
+__device__ __forceinline__ void pair_tile(ctab<PairArgs> A, const int4 tile) {
     constexpr int NOP = ((OPS >> 0) & 1) + ((OPS >> 1) & 1) + ((OPS >> 2) & 1) +
                         ((OPS >> 3) & 1) + ((OPS >> 4) & 1);
     constexpr int NV = J * NOP * (2 + TP);       // accumulators per lane
-    constexpr int SL = 8;                        // accumulators combined per LDS round
+    constexpr int SL = PAIR_SL;
     constexpr int PAIR_SPLIT = pair_split<LIST>();
     __shared__ double red[PAIR_SPLIT - 1][SL][64];
-    const int4 tile = tiles[blockIdx.x];
     const PairArgs& g = tab(A, tile.x);
     DSC_GLOBAL(g.ilist); DSC_GLOBAL(g.Vs); DSC_GLOBAL(g.Rs); DSC_GLOBAL(g.Cs); DSC_GLOBAL(g.Vf); DSC_GLOBAL(g.Rf); DSC_GLOBAL(g.Cf); DSC_GLOBAL(g.mu); DSC_GLOBAL(g.mur); DSC_GLOBAL(g.valid);
     DSC_GLOBAL(g.mat_raw); DSC_GLOBAL(g.Yn); DSC_GLOBAL(g.ysum); DSC_GLOBAL(g.scores); DSC_GLOBAL(g.nscored); DSC_GLOBAL(g.fix_ids); DSC_GLOBAL(g.fix_cnt); DSC_GLOBAL(g.msq);
@@ -640,7 +640,7 @@ __global__ __launch_bounds__(64 * pair_split<LIST>()) void k_screen_pairs(ctab<P
         }
         __syncthreads();
     }
-    if (wave != 0) return;
+    if (wave != 0) return;                       // the epilogue is wave 0's
 
     const double nn = (double)g.n;
     const int64_t ria = g.mat_raw[ic];
@@ -727,6 +727,30 @@ __global__ __launch_bounds__(64 * pair_split<LIST>()) void k_screen_pairs(ctab<P
 #undef S1
 #undef S2
 #undef DT
+}
+
+// One block per tile (grid = tiles), or, with QUEUE, a persistent grid
+// whose blocks take tile after tile from a device work queue (an atomic
+// counter over the list, which is ordered heaviest first) until it runs
+// out.  Either way each tile is computed by one block in the same order of
+// operations, so the scores do not depend on the schedule.
+template <int OPS, int J, int TP, bool LIST, bool QUEUE>
+__global__ __launch_bounds__(64 * pair_split<LIST>()) void k_screen_pairs(ctab<PairArgs> A,
+                                                      const int4* __restrict__ tiles, int64_t n_tiles,
+                                                      unsigned long long* __restrict__ queue) {
+    if (!QUEUE) {
+        pair_tile<OPS, J, TP, LIST>(A, tiles[blockIdx.x]);
+        return;
+    }
+    __shared__ int64_t s_t;
+    for (;;) {
+        if (threadIdx.x == 0) s_t = (int64_t)atomicAdd(queue, 1ull);
+        __syncthreads();
+        const int64_t t = s_t;
+        __syncthreads();
+        if (t >= n_tiles) break;
+        pair_tile<OPS, J, TP, LIST>(A, tiles[t]);
+    }
 }
 
 // -------------------------------------------- reduced-precision screen
@@ -2164,37 +2188,45 @@ static int max_J(int TP) { return TP == 1 ? 4 : TP == 2 ? 2 : 1; }
 
 template <int OPS, int J, int TP>
 static void launch_pairs_t(ctab<PairArgs> A, const int4* tiles, int64_t n, bool list,
-                           hipStream_t st) {
-    if (n == 0) return;                        // one 256-thread block per tile
-    if (list) k_screen_pairs<OPS, 1, TP, true><<<(unsigned)n, 64 * pair_split<true>(), 0, st>>>(A, tiles);
-    else k_screen_pairs<OPS, J, TP, false><<<(unsigned)n, 64 * pair_split<false>(), 0, st>>>(A, tiles);
+                           unsigned long long* queue, hipStream_t st) {
+    if (n == 0) return;
+    if (list) {
+        k_screen_pairs<OPS, 1, TP, true, false><<<(unsigned)n, 64 * pair_split<true>(), 0, st>>>(A, tiles, n, nullptr);
+    } else if (queue) {                        // persistent: 8 blocks per CU at most
+        const unsigned g = (unsigned)std::min<int64_t>(n, 8 * 256);
+        k_screen_pairs<OPS, J, TP, false, true><<<g, 64 * pair_split<false>(), 0, st>>>(A, tiles, n, queue);
+    } else {                                   // one block per tile
+        k_screen_pairs<OPS, J, TP, false, false><<<(unsigned)n, 64 * pair_split<false>(), 0, st>>>(A, tiles, n, nullptr);
+    }
 }
 
 template <int OPS>
 static void launch_pairs_ops(ctab<PairArgs> A, const int4* tiles, int64_t n, bool list, int TP,
-                             int J, hipStream_t st) {
+                             int J, unsigned long long* q, hipStream_t st) {
     switch (TP) {
     case 1:
-        if (J == 4) launch_pairs_t<OPS, 4, 1>(A, tiles, n, list, st);
-        else if (J == 2) launch_pairs_t<OPS, 2, 1>(A, tiles, n, list, st);
-        else launch_pairs_t<OPS, 1, 1>(A, tiles, n, list, st);
+        if (J == 4) launch_pairs_t<OPS, 4, 1>(A, tiles, n, list, q, st);
+        else if (J == 2) launch_pairs_t<OPS, 2, 1>(A, tiles, n, list, q, st);
+        else launch_pairs_t<OPS, 1, 1>(A, tiles, n, list, q, st);
         break;
     case 2:
-        if (J == 2) launch_pairs_t<OPS, 2, 2>(A, tiles, n, list, st);
-        else launch_pairs_t<OPS, 1, 2>(A, tiles, n, list, st);
+        if (J == 2) launch_pairs_t<OPS, 2, 2>(A, tiles, n, list, q, st);
+        else launch_pairs_t<OPS, 1, 2>(A, tiles, n, list, q, st);
         break;
-    case 4: launch_pairs_t<OPS, 1, 4>(A, tiles, n, list, st); break;
-    case 8: launch_pairs_t<OPS, 1, 8>(A, tiles, n, list, st); break;
-    default: launch_pairs_t<OPS, 1, 16>(A, tiles, n, list, st); break;
+    case 4: launch_pairs_t<OPS, 1, 4>(A, tiles, n, list, q, st); break;
+    case 8: launch_pairs_t<OPS, 1, 8>(A, tiles, n, list, q, st); break;
+    default: launch_pairs_t<OPS, 1, 16>(A, tiles, n, list, q, st); break;
     }
 }
 
+// queue: a zeroed device counter to run the dense tiles as one persistent
+// launch over a work queue, or NULL for one block per tile.
 static void launch_pairs(int OPS, ctab<PairArgs> A, const int4* tiles, int64_t n, bool list, int TP,
-                         int J, hipStream_t st) {
+                         int J, hipStream_t st, unsigned long long* queue = nullptr) {
     switch (OPS) {
-    case 31: launch_pairs_ops<31>(A, tiles, n, list, TP, J, st); break;
-    case 28: launch_pairs_ops<28>(A, tiles, n, list, TP, J, st); break;
-    case 3: launch_pairs_ops<3>(A, tiles, n, list, TP, J, st); break;
+    case 31: launch_pairs_ops<31>(A, tiles, n, list, TP, J, queue, st); break;
+    case 28: launch_pairs_ops<28>(A, tiles, n, list, TP, J, queue, st); break;
+    case 3: launch_pairs_ops<3>(A, tiles, n, list, TP, J, queue, st); break;
     default: DSC_FAIL(DISCOVER_E_UNSUPPORTED, "operator class %d", OPS);
     }
 }
@@ -2394,6 +2426,7 @@ struct Problem {
     std::shared_ptr<Plan> plan;
     int n, T, Tl, TP, ldn, ldm, Mc;
     int64_t N, fix_cap;
+    unsigned long long* queues = nullptr;   // the call's work-queue counters (zeroed by its fills)
     double *Vf, *Rf, *Cf, *Vs, *Rs, *Cs, *mu, *mur, *msq, *Yc, *Yn, *syy, *ysum, *scores;
     uint8_t* valid;
     unsigned long long* ctr;                  // [0] bad target (int), [1] fix count, [2] scored, [3] rung-3 fix count
@@ -2513,6 +2546,8 @@ static void layout_problems(discover_ctx* ctx, const discover_problem* probs, in
 
 // Merged dense / list tiles of a call: problems in decreasing n (the
 // heaviest tiles first), each problem's tiles in plan order.
+constexpr int MAX_QUEUES = 64;          // work-queue counters per screen (dense groups)
+
 struct TileGroup {
     int cls, TP, J;
     bool list;
@@ -2527,12 +2562,17 @@ static std::vector<int> by_weight(const std::vector<Problem>& PS) {
     return order;
 }
 
-// Autotuned tile width of a dense group: each admissible J is timed once
-// for this batch signature (every variant writes the same scores; the
-// counters the runs bump are restored), and the fastest is remembered.
+// Autotuned launch of a dense group: tile width J (operand features per
+// wave: 1, 2, 4 as the target count allows) and schedule (one block per
+// tile, or one persistent launch over a device work queue).  Each
+// admissible variant is timed once for the group's shape class -- operator
+// class, padded target count, and the power-of-two buckets of the largest
+// sample count and of the tile count -- with the counter bumps of the trial
+// runs undone (every variant writes the same scores), and the fastest is
+// remembered for that class.  Returns J | queue << 8.
 static int tune_dense(discover_ctx* ctx, const std::string& key, int cls, int TP,
                       ctab<PairArgs> dA, std::vector<Problem>& PS, const std::vector<int>& members,
-                      hipStream_t st) {
+                      int Jfix, int sched, hipStream_t st) {
     auto it = ctx->tuned.find(key);
     if (it != ctx->tuned.end()) return it->second;
     if (ctx->capturing) DSC_FAIL(DISCOVER_E_CAPACITY, "tile autotuning during graph capture");
@@ -2543,30 +2583,42 @@ static int tune_dense(discover_ctx* ctx, const std::string& key, int cls, int TP
         DSC_HIP(hipMemcpyAsync(sv, PS[b].ctr, 32, hipMemcpyDeviceToDevice, st));
         saved.push_back(sv);
     }
+    unsigned long long* q = ctx->buf<unsigned long long>("tune_queue", 1);
     double best = 1e30;
-    int bestJ = 1;
+    int choice = 1;
     for (int jx = 0; jx < 3 && (1 << jx) <= max_J(TP); jx++) {
+        if (Jfix > 0 && (1 << jx) != Jfix) continue;
         std::vector<int4> tiles;
         for (int b : order) {
             if (std::find(members.begin(), members.end(), b) == members.end()) continue;
             for (const int2& t : PS[b].plan->dtilesJ[jx]) tiles.push_back(make_int4(b, t.x, t.y, 0));
         }
         const int4* dt = ctx->upload("tune_tiles", tiles, st);
-        hipEvent_t e0 = ctx->event(), e1 = ctx->event();
-        DSC_HIP(hipEventRecord(e0, st));
-        launch_pairs(cls, dA, dt, (int64_t)tiles.size(), false, TP, 1 << jx, st);
-        DSC_HIP(hipEventRecord(e1, st));
-        for (size_t q = 0; q < members.size(); q++)
-            DSC_HIP(hipMemcpyAsync(PS[members[q]].ctr, saved[q], 32, hipMemcpyDeviceToDevice, st));
-        DSC_HIP(hipEventSynchronize(e1));
-        float ms = 0.f;
-        DSC_HIP(hipEventElapsedTime(&ms, e0, e1));
-        ctx->free_events.push_back(e0);
-        ctx->free_events.push_back(e1);
-        if (ms < best) { best = ms; bestJ = 1 << jx; }
+        for (int qv = 0; qv < 2; qv++) {
+            if ((qv == 1 && sched < 0) || (qv == 0 && sched > 0)) continue;
+            if (qv) fill_all(ctx, "tune_qfill", {fill_seg(q, 8, 0u)}, st);
+            hipEvent_t e0 = ctx->event(), e1 = ctx->event();
+            DSC_HIP(hipEventRecord(e0, st));
+            launch_pairs(cls, dA, dt, (int64_t)tiles.size(), false, TP, 1 << jx, st, qv ? q : nullptr);
+            DSC_HIP(hipEventRecord(e1, st));
+            for (size_t m = 0; m < members.size(); m++)
+                DSC_HIP(hipMemcpyAsync(PS[members[m]].ctr, saved[m], 32, hipMemcpyDeviceToDevice, st));
+            DSC_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            DSC_HIP(hipEventElapsedTime(&ms, e0, e1));
+            ctx->free_events.push_back(e0);
+            ctx->free_events.push_back(e1);
+            if (ms < best) { best = ms; choice = (1 << jx) | (qv << 8); }
+        }
     }
-    ctx->tuned[key] = bestJ;
-    return bestJ;
+    ctx->tuned[key] = choice;
+    return choice;
+}
+
+static int log2_bucket(int64_t v) {
+    int b = 0;
+    while (v > 1) { v >>= 1; b++; }
+    return b;
 }
 
 // Autotuned choice of the precision form for one problem's dense pair
@@ -2608,9 +2660,13 @@ static void screen_all(discover_ctx* ctx, const discover_problem* probs, int nb,
                        const discover_screen_params& prm, std::vector<Problem>& PS, hipStream_t st,
                        const std::function<void(std::vector<FillSeg>&)>& more_fills = nullptr) {
     layout_problems(ctx, probs, nb, prm, PS);
-    // 1. fills: counters, padded target rows, score slots (NaN pattern), rung-2 flags
+    // 1. fills: counters, padded target rows, score slots (NaN pattern), rung-2 flags,
+    // the work-queue counters of the dense groups
     std::vector<FillSeg> fills;
+    unsigned long long* queues = ctx->buf<unsigned long long>("scr_queue" + ctx->tag, MAX_QUEUES);
+    fills.push_back(fill_seg(queues, MAX_QUEUES * 8, 0u));
     for (Problem& P : PS) {
+        P.queues = queues;
         fills.push_back(fill_seg(P.ctr, 32, 0u));
         fills.push_back(fill_seg(P.Yn, (size_t)P.TP * P.ldn * 8, 0u));
         fills.push_back(fill_seg(P.ysum, (size_t)P.TP * 8, 0u));
@@ -2768,19 +2824,30 @@ static void screen_all(discover_ctx* ctx, const discover_problem* probs, int nb,
             groups[{P.plan->dense_cls, P.TP}].push_back(b);
     }
     int gi = 0;
+    unsigned long long* const gqueues = PS.empty() ? nullptr : PS[0].queues;
     for (auto& g : groups) {
         const int cls = g.first.first, TP = g.first.second;
         const std::vector<int>& mem = g.second;
         int J = 1;
+        bool useq = prm.sched > 0;
         if (prm.tile_j > 0) {
             while (J * 2 <= std::min(prm.tile_j, max_J(TP))) J *= 2;
-        } else {
-            std::string key = "dense";
+        }
+        if (prm.tile_j == 0 || prm.sched == 0) {
+            // shape class: operator class, padded targets, buckets of the
+            // largest n and of the tile count
+            int nmax = 0;
+            int64_t nt = 0;
             for (int b : mem) {
-                key += PS[b].plan->key;
-                key.append((const char*)&PS[b].n, sizeof(int));
+                nmax = std::max(nmax, PS[b].n);
+                nt += (int64_t)PS[b].plan->dtilesJ[0].size();
             }
-            J = tune_dense(ctx, key, cls, TP, dpa, PS, mem, st);
+            const std::string key = "dense|" + std::to_string(cls) + "|" + std::to_string(TP) + "|" +
+                                    std::to_string(log2_bucket(nmax)) + "|" + std::to_string(log2_bucket(nt)) +
+                                    "|" + std::to_string(prm.tile_j) + "|" + std::to_string(prm.sched);
+            const int c = tune_dense(ctx, key, cls, TP, dpa, PS, mem, prm.tile_j > 0 ? J : 0, prm.sched, st);
+            if (prm.tile_j == 0) J = c & 0xFF;
+            if (prm.sched == 0) useq = (c >> 8) != 0;
         }
         const int jx = J == 4 ? 2 : J == 2 ? 1 : 0;
         std::vector<int4> tiles;
@@ -2788,10 +2855,12 @@ static void screen_all(discover_ctx* ctx, const discover_problem* probs, int nb,
             PS[b].tile_j = J;
             for (const int2& t : PS[b].plan->dtilesJ[jx]) tiles.push_back(make_int4(b, t.x, t.y, 0));
         }
-        const int4* dt = ctx->upload("scr_dtiles" + std::to_string(gi++), tiles, st);
+        const int4* dt = ctx->upload("scr_dtiles" + std::to_string(gi), tiles, st);
         KTimer kt(ctx, st, "screen_pairs");
-        launch_pairs(cls, dpa, dt, (int64_t)tiles.size(), false, TP, J, st);
+        if (useq && gi >= MAX_QUEUES) useq = false;   // (more groups than queue counters)
+        launch_pairs(cls, dpa, dt, (int64_t)tiles.size(), false, TP, J, st, useq ? gqueues + gi : nullptr);
         check_launch("k_screen_pairs");
+        gi++;
     }
     // 6c. same-unit add/sub partner lists (FP64 in every form), merged per TP
     std::map<int, std::vector<int4>> lgroups;
@@ -3039,6 +3108,7 @@ static void validate(const discover_problem* probs, int32_t nb, const discover_s
                 "precision %d", prm->precision);
     DSC_REQUIRE(prm->tile_j >= 0 && prm->tile_j <= 4, "tile_j %d outside 0..4", prm->tile_j);
     DSC_REQUIRE(prm->lp_pairs >= -1 && prm->lp_pairs <= 1, "lp_pairs %d outside -1..1", prm->lp_pairs);
+    DSC_REQUIRE(prm->sched >= -1 && prm->sched <= 1, "sched %d outside -1..1", prm->sched);
     for (int r = 1; r <= prm->rung; r++) {
         DSC_REQUIRE((prm->rung_ops[r] & ~DISCOVER_OPS_ALL) == 0, "unknown operator bits at rung %d", r);
         DSC_REQUIRE(prm->rung_pool[r] >= -1 && prm->rung_pool[r] < r, "rung_pool[%d]", r);

@@ -69,6 +69,30 @@ def test_batch_screen_equals_single(torch, ctx, D, T, mode, R):
             assert st[key] == bst[key], (b, key)
 
 
+@pytest.mark.parametrize("T", [1, 3])
+def test_batch_schedule_invariant(torch, ctx, D, T):
+    """Datasets of uneven n and p screened in one call: the dense tiles run
+    one block per tile, as one persistent launch over a device work queue,
+    or as the autotuner chooses, with bit-identical selections, values and
+    counts."""
+    data = _datasets(31 + T, 9, T)
+    Xs = [dev(torch, X) for X, _ in data]
+    Ys = [dev(torch, Y) for _, Y in data]
+    out = {}
+    for sched in (-1, 1, 0):
+        prm = D.params(rung=2, k=25, sched=sched)
+        out[sched] = ctx.generate_screen_batch(Xs, Ys, prm)
+    for sched in (1, 0):
+        for b in range(len(data)):
+            ri, rs, rv, rst = out[-1][b]
+            bi, bs, bv, bst = out[sched][b]
+            assert np.array_equal(ri.cpu().numpy(), bi.cpu().numpy()), (sched, b)
+            assert np.array_equal(_bits(rs), _bits(bs)), (sched, b)
+            assert np.array_equal(_bits(rv), _bits(bv)), (sched, b)
+            for key in ("n_raw", "n_unit_valid", "n_scored", "n_selected", "n_merged"):
+                assert rst[key] == bst[key], (sched, b, key)
+
+
 def test_batch_screen_units_exclude_mixed(torch, ctx, D):
     """Datasets with and without units, with exclusion lists, in one call."""
     rng = np.random.default_rng(5)

@@ -163,8 +163,10 @@ def test_screen_duplicates_second_round(torch, ctx, D, oracle_mod):
 
 @pytest.mark.parametrize("T", [1, 2, 3])
 def test_tile_width_invariant(torch, ctx, D, T):
-    """The dense pair kernel's tile width (forced 1/2/4, or autotuned) does
-    not change a single bit of the scores or the selection."""
+    """The dense pair kernel's tile width (forced 1/2/4, or autotuned) and
+    its schedule (one block per tile, or one persistent launch over a device
+    work queue, or autotuned) do not change a single bit of the selected
+    IDs, scores or values, nor the counts."""
     rng = np.random.default_rng(77 + T)
     p, n = 11, 203
     X = rng.lognormal(0, 0.5, size=(p, n))
@@ -172,17 +174,25 @@ def test_tile_width_invariant(torch, ctx, D, T):
     Xd, Yd = dev(torch, X), dev(torch, Y)
     runs = {}
     for tj in (0, 1, 2, 4):
-        ids, sc, vals, st = ctx.generate_screen(Xd, Yd, D.params(rung=2, k=60, tile_j=tj))
-        runs[tj] = (ids.cpu().numpy(), sc.cpu().numpy(), st["tile_j"])
+        for sched in (0, -1, 1):
+            ids, sc, vals, st = ctx.generate_screen(Xd, Yd, D.params(rung=2, k=60, tile_j=tj, sched=sched))
+            runs[tj, sched] = (ids.cpu().numpy(), sc.cpu().numpy(), st["tile_j"], vals.cpu().numpy(),
+                               st["n_scored"], st["n_unit_valid"])
     widest = {1: 4, 2: 2}.get(T, 1)
-    for tj in (1, 2, 4):
-        assert runs[tj][2] == min(tj, widest)
-        assert np.array_equal(runs[tj][0], runs[1][0])
-        assert np.array_equal(runs[tj][1].view(np.int64), runs[1][1].view(np.int64))
-    assert runs[0][2] in (1, 2, 4) and runs[0][2] <= widest
-    assert np.array_equal(runs[0][0], runs[1][0])
+    ref = runs[1, -1]
+    for (tj, sched), r in runs.items():
+        if tj:
+            assert r[2] == min(tj, widest)
+        else:
+            assert r[2] in (1, 2, 4) and r[2] <= widest
+        assert np.array_equal(r[0], ref[0]), (tj, sched)
+        assert np.array_equal(r[1].view(np.int64), ref[1].view(np.int64)), (tj, sched)
+        assert np.array_equal(r[3].view(np.int64), ref[3].view(np.int64)), (tj, sched)
+        assert r[4:] == ref[4:], (tj, sched)
     with pytest.raises(D.DiscoverError):
         ctx.generate_screen(Xd, Yd, D.params(rung=2, k=60, tile_j=5))
+    with pytest.raises(D.DiscoverError):
+        ctx.generate_screen(Xd, Yd, D.params(rung=2, k=60, sched=2))
 
 
 def test_screen_exclusion(torch, ctx, D, oracle_mod):
