@@ -998,3 +998,221 @@ void or_set_threads(int t) {
     (void)t;
 #endif
 }
+
+/* ------------------------------------------------------------------------ */
+/* Simulated annealing over D-subsets                                        */
+/* ------------------------------------------------------------------------ */
+/* The paper names simulated annealing among the stochastic strategies for
+ * the sparsifying step (Software Description) when exhaustive L0 over the
+ * subsets of Eq. (1) is out of reach.  The reading implemented here:
+ *
+ *   state    a D-subset a[0..D-1] of the S rows (an ordered array);
+ *   energy   E(a) = 1 - R^2 of the least-squares fit of y on [1, rows a],
+ *            from the correlation matrix: E = 1 - c_a^T C_aa^{-1} c_a, by
+ *            Cholesky of C_aa in array order; a pivot at or below 1e-10
+ *            (R10) makes the subset singular, E = +inf;
+ *   move     a uniform position p of the array and a uniform row r; a row
+ *            already in the subset leaves the state unchanged;
+ *   accept   Metropolis: E' <= E, or u < exp(-(E' - E) / T) for a uniform
+ *            u in [0, 1); T starts at T0 and is multiplied by alpha after
+ *            every proposal (geometric cooling);
+ *   chains   independent, each with its own random stream; each keeps its
+ *            best state (smallest E, ties: the smaller sorted candidate-ID
+ *            tuple), and the problem's result is the best over chains.
+ *
+ * Random numbers: the SplitMix64 generator (Steele, Lea and Flood, OOPSLA
+ * 2014), used counter-based.  Output i (i >= 1) of the stream with state
+ * x0 is mix(x0 + i * 0x9E3779B97F4A7C15).  Chain q's key is output q + 1
+ * of the stream with state seed; its draw number c is output c + 1 of the
+ * stream with state key.  A row draw is draw mod S, a uniform is
+ * (draw >> 11) * 2^-53.
+ *
+ * Every quantity that decides a move (correlations, Cholesky, exp) is
+ * computed in IEEE double with one rounding per operation (no fused
+ * multiply-add, built with -ffp-contract=off), in a fixed order, so that
+ * an implementation that does the same obtains the same trajectory bit for
+ * bit.  exp(-x) is evaluated by the range reduction x = k ln 2 + r and the
+ * Taylor series of exp(-r) to degree 18 in Horner form (an approximation
+ * of exp accurate to a few ulps; the same function on both sides is what
+ * matters for the trajectory).
+ */
+static const uint64_t SM_GAMMA = 0x9E3779B97F4A7C15ull;
+
+uint64_t or_splitmix_mix(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+/* Output i (i >= 1) of the SplitMix64 stream with state x0. */
+uint64_t or_splitmix_at(uint64_t x0, uint64_t i) { return or_splitmix_mix(x0 + i * SM_GAMMA); }
+
+static uint64_t sa_draw(uint64_t key, uint64_t c) { return or_splitmix_at(key, c + 1); }
+
+double or_sa_exp_neg(double x) {
+    if (!(x < 700.0)) return 0.0;
+    if (x <= 0.0) return 1.0;
+    const double LN2 = 0.6931471805599453;
+    const double INV_LN2 = 1.4426950408889634;
+    const int k = (int)(x * INV_LN2);
+    const double t = (double)k * LN2;
+    const double r = x - t;
+    double p = 1.0;
+    for (int i = 18; i >= 1; i--) {
+        double q = p * -r;
+        q = q / (double)i;
+        p = 1.0 + q;
+    }
+    return ldexp(p, -k);
+}
+
+/* Correlation matrix in the fixed order the annealing reads: per row, the
+ * mean as a left-to-right sum over samples divided by n, centred values,
+ * norm = sqrt of the left-to-right sum of squares; C[i][j] = (left-to-right
+ * sum of z_i z_j) / (norm_i * norm_j), c[i] the same with the centred
+ * target; a constant row gets norm 0 and C = c = 0 in its row and column. */
+void or_sa_corr(int n, int S, const double* F, const double* y, double* C, double* c) {
+    double* Z = (double*)malloc(sizeof(double) * (size_t)(S + 1) * n);
+    double* nrm = (double*)malloc(sizeof(double) * (size_t)(S + 1));
+    for (int i = 0; i <= S; i++) {
+        const double* f = i < S ? F + (size_t)i * n : y;
+        double s = 0.0;
+        for (int t = 0; t < n; t++) s = s + f[t];
+        const double m = s / (double)n;
+        double q = 0.0;
+        for (int t = 0; t < n; t++) {
+            const double d = f[t] - m;
+            Z[(size_t)i * n + t] = d;
+            q = q + d * d;
+        }
+        nrm[i] = sqrt(q);
+    }
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int i = 0; i < S; i++) {
+        for (int j = 0; j <= S; j++) {
+            double v = 0.0;
+            if (nrm[i] > 0.0 && nrm[j] > 0.0) {
+                double d = 0.0;
+                for (int t = 0; t < n; t++) d = d + Z[(size_t)i * n + t] * Z[(size_t)j * n + t];
+                v = d / (nrm[i] * nrm[j]);
+            }
+            if (j < S) C[(size_t)i * S + j] = v;
+            else c[i] = v;
+        }
+    }
+    free(Z);
+    free(nrm);
+}
+
+/* E = 1 - R^2 of the subset a (array order), +inf when singular. */
+double or_sa_energy(int S, const double* C, const double* c, int D, const int* a) {
+    double L[8][8], w[8];
+    for (int j = 0; j < D; j++) {
+        double d = C[(size_t)a[j] * S + a[j]];
+        for (int k = 0; k < j; k++) d = d - L[j][k] * L[j][k];
+        if (!(d > 1e-10)) return INFINITY;
+        const double ljj = sqrt(d);
+        L[j][j] = ljj;
+        for (int i = j + 1; i < D; i++) {
+            double v = C[(size_t)a[i] * S + a[j]];
+            for (int k = 0; k < j; k++) v = v - L[i][k] * L[j][k];
+            L[i][j] = v / ljj;
+        }
+    }
+    double ex = 0.0;
+    for (int j = 0; j < D; j++) {
+        double v = c[a[j]];
+        for (int k = 0; k < j; k++) v = v - L[j][k] * w[k];
+        w[j] = v / L[j][j];
+        ex = ex + w[j] * w[j];
+    }
+    return 1.0 - ex;
+}
+
+static void sort_rows(int D, int* s) {
+    for (int i = 1; i < D; i++)
+        for (int j = i; j > 0 && s[j] < s[j - 1]; j--) { int t = s[j]; s[j] = s[j - 1]; s[j - 1] = t; }
+}
+
+/* ID tuple of sorted rows a before that of b (rows are sorted by row index;
+ * the tuples compare by sorted candidate ID). */
+static int ids_before(int D, const int* a, const int* b, const int64_t* ids) {
+    int64_t ia[8], ib[8];
+    for (int i = 0; i < D; i++) { ia[i] = ids[a[i]]; ib[i] = ids[b[i]]; }
+    for (int i = 1; i < D; i++)
+        for (int j = i; j > 0; j--) {
+            if (ia[j] < ia[j - 1]) { int64_t t = ia[j]; ia[j] = ia[j - 1]; ia[j - 1] = t; }
+            if (ib[j] < ib[j - 1]) { int64_t t = ib[j]; ib[j] = ib[j - 1]; ib[j - 1] = t; }
+        }
+    for (int i = 0; i < D; i++)
+        if (ia[i] != ib[i]) return ia[i] < ib[i];
+    return 0;
+}
+
+/* Annealing of Q chains; chain q's best subset (rows ascending) goes to
+ * best + q D and its energy to best_e[q]; init (D rows) or NULL for a
+ * random start (rows drawn with draws 0, 1, ... of the chain, repeats
+ * skipped).  Proposal k uses draws 2^40 + 3k (position), + 1 (row), + 2
+ * (uniform).  Returns the chain holding the overall best. */
+int or_sa_run(int S, const double* C, const double* c, const int64_t* ids, int D, int Q,
+              int64_t K, double T0, double alpha, uint64_t seed, const int* init, int* best,
+              double* best_e) {
+    if (D < 1 || D > 8 || D > S || Q < 1) return -1;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int q = 0; q < Q; q++) {
+        const uint64_t key = or_splitmix_at(seed, (uint64_t)q + 1);
+        int a[8], b[8], bs[8];
+        if (init) {
+            for (int j = 0; j < D; j++) a[j] = init[j];
+        } else {
+            uint64_t ctr = 0;
+            for (int j = 0; j < D; j++) {
+                for (;;) {
+                    const int r = (int)(sa_draw(key, ctr++) % (uint64_t)S);
+                    int dup = 0;
+                    for (int i = 0; i < j; i++) dup |= a[i] == r;
+                    if (!dup) { a[j] = r; break; }
+                }
+            }
+        }
+        double E = or_sa_energy(S, C, c, D, a);
+        double bE = E;
+        for (int j = 0; j < D; j++) bs[j] = a[j];
+        sort_rows(D, bs);
+        double T = T0;
+        const uint64_t base = (uint64_t)1 << 40;
+        for (int64_t k = 0; k < K; k++) {
+            const int p = (int)(sa_draw(key, base + 3 * (uint64_t)k) % (uint64_t)D);
+            const int r = (int)(sa_draw(key, base + 3 * (uint64_t)k + 1) % (uint64_t)S);
+            const double u = (double)(sa_draw(key, base + 3 * (uint64_t)k + 2) >> 11) * 0x1.0p-53;
+            int in = 0;
+            for (int j = 0; j < D; j++) in |= a[j] == r;
+            if (!in) {
+                for (int j = 0; j < D; j++) b[j] = a[j];
+                b[p] = r;
+                const double En = or_sa_energy(S, C, c, D, b);
+                int acc = En <= E;
+                if (!acc && En < INFINITY) acc = u < or_sa_exp_neg((En - E) / T);
+                if (acc) {
+                    for (int j = 0; j < D; j++) a[j] = b[j];
+                    E = En;
+                    int sa[8];
+                    for (int j = 0; j < D; j++) sa[j] = a[j];
+                    sort_rows(D, sa);
+                    if (E < bE || (E == bE && ids_before(D, sa, bs, ids))) {
+                        bE = E;
+                        for (int j = 0; j < D; j++) bs[j] = sa[j];
+                    }
+                }
+            }
+            T = T * alpha;
+        }
+        for (int j = 0; j < D; j++) best[(size_t)q * D + j] = bs[j];
+        best_e[q] = bE;
+    }
+    int w = 0;
+    for (int q = 1; q < Q; q++)
+        if (best_e[q] < best_e[w] || (best_e[q] == best_e[w] && ids_before(D, best + (size_t)q * D, best + (size_t)w * D, ids)))
+            w = q;
+    return w;
+}

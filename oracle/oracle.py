@@ -108,6 +108,17 @@ def lib():
         L.or_l0_gram_band.restype = C.c_int64
         L.or_l0_gram_band.argtypes = [C.c_int, P, P, C.c_int, C.c_double, C.c_int,
                                       C.c_double, C.c_int64, P, P]
+        L.or_splitmix_at.restype = C.c_uint64
+        L.or_splitmix_at.argtypes = [C.c_uint64, C.c_uint64]
+        L.or_sa_exp_neg.restype = C.c_double
+        L.or_sa_exp_neg.argtypes = [C.c_double]
+        L.or_sa_corr.restype = None
+        L.or_sa_corr.argtypes = [C.c_int, C.c_int, P, P, P, P]
+        L.or_sa_energy.restype = C.c_double
+        L.or_sa_energy.argtypes = [C.c_int, P, P, C.c_int, P]
+        L.or_sa_run.restype = C.c_int
+        L.or_sa_run.argtypes = [C.c_int, P, P, P, C.c_int, C.c_int, C.c_int64, C.c_double,
+                                C.c_double, C.c_uint64, P, P, P]
         L.or_max_threads.restype = C.c_int
         L.or_set_threads.restype = None
         L.or_set_threads.argtypes = [C.c_int]
@@ -452,6 +463,49 @@ def corr_matrix(F, y):
     yy = np.zeros(1, np.float64)
     lib().or_corr_matrix(n, S, _p(F), _p(y), _p(Cm), _p(c), _p(yy))
     return Cm, c, float(yy[0])
+
+
+def sa_corr(F, y):
+    """Correlation matrix and target correlations in the fixed order the
+    annealing reads (left-to-right sums, one rounding per operation)."""
+    F = np.ascontiguousarray(F, np.float64)
+    y = np.ascontiguousarray(y, np.float64)
+    S, n = F.shape
+    Cm = np.empty((S, S), np.float64)
+    c = np.empty(S, np.float64)
+    lib().or_sa_corr(n, S, _p(F), _p(y), _p(Cm), _p(c))
+    return Cm, c
+
+
+def sa_energy(Cm, c, rows):
+    """1 - R^2 of the subset `rows` (array order) from sa_corr's matrices;
+    inf when a Cholesky pivot is at or below 1e-10."""
+    a = np.ascontiguousarray(rows, np.int32)
+    return float(lib().or_sa_energy(Cm.shape[0], _p(Cm), _p(c), len(a), _p(a)))
+
+
+def anneal(F, ids, y, D, chains, steps, T0, alpha, seed, init=None):
+    """Simulated annealing over D-subsets of the rows of F (the
+    stochastic search the paper names for the sparsifying step, Software
+    Description): `chains` independent Metropolis chains of `steps`
+    single-row swaps under geometric cooling T0 * alpha^k, random numbers
+    from counter-based SplitMix64 (or_sa_run states every rule).  Returns
+    (winning chain, best rows of every chain [chains][D] ascending, their
+    energies 1 - R^2 [chains])."""
+    Cm, c = sa_corr(F, y)
+    S = Cm.shape[0]
+    ids = np.ascontiguousarray(ids, np.int64)
+    best = np.zeros((chains, D), np.int32)
+    be = np.zeros(chains, np.float64)
+    ini = None
+    if init is not None:
+        ini = np.ascontiguousarray(init, np.int32)
+        assert len(ini) == D and len(set(ini.tolist())) == D and ini.min() >= 0 and ini.max() < S
+    w = lib().or_sa_run(S, _p(Cm), _p(c), _p(ids), D, chains, int(steps), float(T0), float(alpha),
+                        int(seed) & 0xFFFFFFFFFFFFFFFF, _p(ini), _p(best), _p(be))
+    if w < 0:
+        raise ValueError("anneal: D must be in 1..8 and at most S, chains >= 1")
+    return int(w), best, be
 
 
 def _rank_models(cands, m, yy):
