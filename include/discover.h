@@ -284,6 +284,56 @@ discover_status discover_omp(discover_ctx* ctx, const discover_l0_problem* probs
                              int32_t* out_active, double* out_coef, double* out_rmse,
                              double* out_resid, int64_t ldr, void* stream);
 
+/* Parameters of the annealing search (discover_l0_anneal). */
+typedef struct {
+    int32_t chains;           /* independent chains per problem, 1..2^20 (thousands fill the GPU) */
+    int32_t reserved;         /* 0 */
+    int64_t steps;            /* proposals per chain, >= 0 */
+    double T0;                /* initial temperature, in units of the energy 1 - R^2, >= 0 */
+    double alpha;             /* cooling factor per proposal, 0 < alpha <= 1 */
+    uint64_t seed;            /* random stream (SplitMix64, counter-based) */
+} discover_anneal_params;
+
+/* Simulated annealing over D-subsets of each subspace (a stochastic search
+ * for the L0 problem of Eq. (1), Core Optimization Objective; named among
+ * the search strategies in Software Description), for D up to 8 or
+ * subspaces too large for exhaustive L0.  Each of `chains` independent
+ * chains starts from init_active (the same rows for every chain) or from
+ * random rows, and makes `steps` proposals: replace the row at a uniform
+ * position by a uniform row (a row already in the subset: no move), accept
+ * when the energy E = 1 - R^2 of the fit of y on [1, rows] does not rise, or
+ * with probability exp(-(E' - E) / T), T = T0 alpha^k.  E comes from the
+ * correlation matrix by Cholesky; a pivot <= 1e-10 makes the subset
+ * singular (E = +inf).  Each chain keeps the best subset it visited (ties:
+ * the smaller sorted candidate-ID tuple); the problem's result is the best
+ * over chains, refitted by Householder QR.  Every rule, and the random
+ * stream (chain q's key = output q + 1 of SplitMix64 with state seed; draw
+ * c = output c + 1 with state key; random starts use draws 0, 1, ...,
+ * proposal k uses draws 2^40 + 3k, + 1, + 2), is computed with one IEEE
+ * rounding per operation, so the same seed gives the same result on every
+ * run and on an implementation that follows the same rules.
+ *
+ *   probs            host [n_problems]; S <= 16384 rows, n >= D + 2
+ *   D                1..DISCOVER_MAX_D
+ *   init_active      device int32 [n_problems][D] distinct rows 0..S-1, or NULL (random
+ *                    starts); a problem whose rows are not distinct and in range starts
+ *                    randomly
+ *   out_subsets      device int32 [n_problems][D] rows of the best subset, ascending
+ *   out_rmse         device double [n_problems] sqrt(RSS / n) of its QR fit
+ *   out_coef         device double [n_problems][D+1] intercept first, then the rows
+ *   out_energy       device double [n_problems] its energy 1 - R^2 as the chains computed it
+ *   out_chain_subsets device int32 [n_problems][chains][D] every chain's best, or NULL
+ *   out_chain_energy device double [n_problems][chains], or NULL
+ *   out_resid        device double [n_problems][ldr] residuals of the QR fit, or NULL
+ * The call does not wait for the stream and can be captured.
+ * Errors: E_ARG, E_NOMEM, E_HIP. */
+discover_status discover_l0_anneal(discover_ctx* ctx, const discover_l0_problem* probs,
+                                   int32_t n_problems, int32_t D, const discover_anneal_params* prm,
+                                   const int32_t* init_active, int32_t* out_subsets, double* out_rmse,
+                                   double* out_coef, double* out_energy, int32_t* out_chain_subsets,
+                                   double* out_chain_energy, double* out_resid, int64_t ldr,
+                                   void* stream);
+
 /* discover_omp for callers that cannot allocate device memory (code under
  * graph capture, tight serving loops, harnesses that forbid allocation):
  * the same arguments, kernels and results, with the work buffers taken

@@ -65,12 +65,17 @@ class L0Stats(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class AnnealParams(C.Structure):
+    _fields_ = [("chains", C.c_int32), ("reserved", C.c_int32), ("steps", C.c_int64),
+                ("T0", C.c_double), ("alpha", C.c_double), ("seed", C.c_uint64)]
+
+
 # Every symbol include/discover.h declares.
 SYMBOLS = ("discover_create", "discover_destroy", "discover_last_error",
            "discover_generate_screen", "discover_l0_fit", "discover_omp", "discover_count",
            "discover_decode", "discover_set_timing", "discover_timing", "discover_reset_timing",
            "discover_sisso_batch", "discover_set_graph_timing", "discover_set_fixup_capacity",
-           "discover_reserve", "discover_omp_noalloc")
+           "discover_reserve", "discover_omp_noalloc", "discover_l0_anneal")
 
 _lib = None
 
@@ -97,6 +102,8 @@ def lib():
         L.discover_omp.argtypes = [P, C.POINTER(L0Problem), C.c_int32, C.c_int32, P, C.c_int32,
                                    P, P, P, P, C.c_int64, P]
         L.discover_omp_noalloc.argtypes = L.discover_omp.argtypes
+        L.discover_l0_anneal.argtypes = [P, C.POINTER(L0Problem), C.c_int32, C.c_int32,
+                                         C.POINTER(AnnealParams), P, P, P, P, P, P, P, P, C.c_int64, P]
         L.discover_count.argtypes = [C.c_int32, C.POINTER(ScreenParams)]
         L.discover_count.restype = C.c_int64
         L.discover_decode.argtypes = [C.c_int32, C.POINTER(ScreenParams), C.c_int64, C.c_char_p,
@@ -330,6 +337,52 @@ class Context:
         (subsets [m][D] rows, rmse [m], coef [m][D+1], resid [m][n], stats)."""
         ((sub, rmse, coef, res, st),) = self.l0_fit_batch([F], [ids], [y], D, m, resid, device_stats)
         return sub, rmse, coef, res, st
+
+    def anneal_batch(self, Fs, idss, ys, D, chains=4096, steps=10000, T0=0.01, alpha=0.9995, seed=0,
+                     inits=None, chain_results=False, resid=False):
+        """Simulated annealing over D-subsets of many subspaces in one call
+        (discover_l0_anneal): Fs[b] [S_b][n_b], idss[b] [S_b] int64, ys[b]
+        [n_b] (CUDA); inits: [nb][D] int32 rows or None.  Returns per dataset
+        (rows [D] ascending, rmse, coef [D+1], energy, chain rows [chains][D]
+        or None, chain energies [chains] or None, resid [n] or None)."""
+        torch = self.torch
+        nb = len(Fs)
+        Fs = [f.contiguous() for f in Fs]
+        idss = [i.contiguous() for i in idss]
+        ys = [y.contiguous() for y in ys]
+        dev = Fs[0].device
+        nmax = max(f.shape[1] for f in Fs)
+        rows = torch.empty((nb, D), dtype=torch.int32, device=dev)
+        rmse = torch.empty(nb, dtype=torch.float64, device=dev)
+        coef = torch.empty((nb, D + 1), dtype=torch.float64, device=dev)
+        en = torch.empty(nb, dtype=torch.float64, device=dev)
+        crow = torch.empty((nb, chains, D), dtype=torch.int32, device=dev) if chain_results else None
+        cen = torch.empty((nb, chains), dtype=torch.float64, device=dev) if chain_results else None
+        res = torch.empty((nb, nmax), dtype=torch.float64, device=dev) if resid else None
+        pbs = (L0Problem * nb)()
+        for b in range(nb):
+            S, n = Fs[b].shape
+            pbs[b].n, pbs[b].S, pbs[b].F, pbs[b].ldf = n, S, Fs[b].data_ptr(), n
+            pbs[b].ids, pbs[b].y = idss[b].data_ptr(), ys[b].data_ptr()
+        ini = None
+        if inits is not None:
+            ini = torch.as_tensor(inits, dtype=torch.int32, device=dev).reshape(nb, D).contiguous()
+        prm = AnnealParams(chains, 0, steps, T0, alpha, seed & 0xFFFFFFFFFFFFFFFF)
+        _check(lib().discover_l0_anneal(self.h, pbs, nb, D, C.byref(prm),
+                                        ini.data_ptr() if ini is not None else None, rows.data_ptr(),
+                                        rmse.data_ptr(), coef.data_ptr(), en.data_ptr(),
+                                        crow.data_ptr() if crow is not None else None,
+                                        cen.data_ptr() if cen is not None else None,
+                                        res.data_ptr() if res is not None else None, nmax,
+                                        _stream_handle(torch, dev)))
+        return [(rows[b], rmse[b], coef[b], en[b], crow[b] if crow is not None else None,
+                 cen[b] if cen is not None else None,
+                 res[b, :Fs[b].shape[1]] if res is not None else None) for b in range(nb)]
+
+    def anneal(self, F, ids, y, D, **kw):
+        """anneal_batch for one subspace."""
+        inits = kw.pop("init", None)
+        return self.anneal_batch([F], [ids], [y], D, inits=None if inits is None else [inits], **kw)[0]
 
     def omp_noalloc(self, F, ids, y, D_max, init=None):
         """``omp`` through the allocation-free entry point (work space in the

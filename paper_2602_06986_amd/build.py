@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdiscover.so")
 SOURCES = ["dsc_abi.cpp", "dsc_space.cpp", "dsc_screen.hip", "dsc_r3.hip", "dsc_l0.hip", "dsc_batch.hip",
-           "dsc_noalloc.hip"]
+           "dsc_noalloc.hip", "dsc_anneal.hip"]
 ARCH = os.environ.get("DISCOVER_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -28,7 +28,10 @@ FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-x", "hip",
 # accumulators in VGPRs (otherwise they are copied between VGPRs and AGPRs
 # on every chunk).
 EXTRA = {"dsc_l0.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
-         "dsc_r3.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
+         "dsc_r3.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
+         # the annealing's decisions: one rounding per operation (no fused
+         # multiply-add), so that its trajectory can be reproduced exactly
+         "dsc_anneal.hip": ["-ffp-contract=off"]}
 
 
 def _obj(src):

@@ -153,6 +153,9 @@ void omp_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int 
 // (the device must be current).
 void noalloc_init(int device);
 size_t omp_scratch_bytes(const discover_l0_problem* probs, int nb, int D_max, bool resid);
+void fit_rows(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D, const int32_t* rows,
+              int64_t rows_ld, double* coef, int64_t coef_ld, double* rmse, double* resid, int64_t ldr,
+              hipStream_t st);
 void validate_omp(const discover_l0_problem* probs, int32_t n_problems, int32_t D_max,
                   const int32_t* init_active, int32_t n_init, const int32_t* out_active,
                   const double* out_coef, const double* out_rmse, const double* out_resid, int64_t ldr);

@@ -1765,6 +1765,30 @@ void omp_batch(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int 
     }
 }
 
+// Householder QR fit of y on [1, the D given rows] for every problem (the
+// OMP fit kernel with no pick): coefficients (intercept first, then the rows
+// in the given order), sqrt(RSS / n), residuals when resid is given.
+void fit_rows(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D, const int32_t* rows,
+              int64_t rows_ld, double* coef, int64_t coef_ld, double* rmse, double* resid, int64_t ldr,
+              hipStream_t st) {
+    int32_t* cnt = ctx->buf<int32_t>("fit_rows_d" + ctx->tag, 1);
+    fill_all(ctx, "fit_rows_fill", {fill_seg(cnt, 4, (uint32_t)D)}, st);
+    for (int b = 0; b < nb; b++) {
+        const discover_l0_problem& pb = probs[b];
+        double* A = ctx->buf<double>("fit_rows_A" + std::to_string(b) + ctx->tag, (size_t)(D + 2) * pb.n);
+        double* rs = ctx->buf<double>("fit_rows_rss" + std::to_string(b) + ctx->tag, 1);
+        double* r = resid ? resid + (int64_t)b * ldr
+                          : ctx->buf<double>("fit_rows_r" + std::to_string(b) + ctx->tag, pb.n);
+        const size_t qr_bytes = (size_t)(D + 2) * pb.n * sizeof(double);
+        const int qr_lds = qr_bytes <= 65536 ? 1 : 0;
+        // the rows are not modified: the kernel only appends when it picks
+        k_omp_fit<<<1, 256, qr_lds ? qr_bytes : 0, st>>>(pb.n, pb.F, pb.ldf, pb.y, (int32_t*)rows + b * rows_ld,
+                                                       cnt, A, coef + b * coef_ld, rs, r, qr_lds, pb.S, nullptr,
+                                                       pb.ids, nullptr, rmse + b);
+    }
+    check_launch("k_omp_fit (rows)");
+}
+
 void validate_omp(const discover_l0_problem* probs, int32_t n_problems, int32_t D_max,
                   const int32_t* init_active, int32_t n_init, const int32_t* out_active,
                   const double* out_coef, const double* out_rmse, const double* out_resid, int64_t ldr) {
