@@ -145,6 +145,7 @@ extern "C" discover_status discover_timing(discover_ctx* ctx, const char* kernel
     using namespace dsc;
     return guarded([&] {
         DSC_REQUIRE(ctx && kernel && launches && total_ms, "arguments");
+        ctx->resolve_timing();               // kernels of calls that did not wait
         auto it = ctx->times.find(kernel);
         *launches = it == ctx->times.end() ? 0 : it->second.first;
         *total_ms = it == ctx->times.end() ? 0.0 : it->second.second;
@@ -155,6 +156,7 @@ extern "C" discover_status discover_reset_timing(discover_ctx* ctx) {
     using namespace dsc;
     return guarded([&] {
         DSC_REQUIRE(ctx, "ctx is NULL");
+        ctx->resolve_timing();
         ctx->times.clear();
     });
 }

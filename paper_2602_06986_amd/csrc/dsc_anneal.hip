@@ -168,6 +168,69 @@ __device__ __forceinline__ double energy(const double* __restrict__ C, const dou
     return 1.0 - ex;
 }
 
+// The same energy for a chain that keeps its factor: M holds C[a_i][a_j]
+// (i >= j) of the current subset, L its Cholesky factor and w the forward
+// solution.  A proposal that replaces a[p] reloads only the D correlations
+// of the new row; of the factor only row p (columns before p) and the
+// columns from p on change, and each entry is recomputed with exactly the
+// operations of the full computation (same values, bit for bit), as are
+// the forward solution and the explained fraction from p on.
+template <int D>
+struct Factor {
+    double M[D][D], L[D][D], w[D], ex[D + 1];   // ex[j]: explained fraction of rows < j
+    bool ok[D + 1];                             // ok[j]: rows < j non-singular
+};
+
+template <int D>
+__device__ __forceinline__ void factor_from(Factor<D>& f, int p) {
+#pragma unroll
+    for (int j = 0; j < D; j++) {
+        if (j < p) {
+            // columns before p: only row p's entry depends on the new row
+            if (!f.ok[j + 1]) continue;
+            double v = f.M[p][j];
+#pragma unroll
+            for (int k = 0; k < j; k++) v = v - f.L[p][k] * f.L[j][k];
+            f.L[p][j] = v / f.L[j][j];
+            continue;
+        }
+        f.ok[j + 1] = false;
+        if (!f.ok[j]) continue;
+        double d = f.M[j][j];
+#pragma unroll
+        for (int k = 0; k < j; k++) d = d - f.L[j][k] * f.L[j][k];
+        if (!(d > 1e-10)) continue;
+        const double ljj = sqrt(d);
+        f.L[j][j] = ljj;
+#pragma unroll
+        for (int i = j + 1; i < D; i++) {
+            double v = f.M[i][j];
+#pragma unroll
+            for (int k = 0; k < j; k++) v = v - f.L[i][k] * f.L[j][k];
+            f.L[i][j] = v / ljj;
+        }
+        f.ok[j + 1] = true;
+    }
+}
+
+// Forward solution and explained fraction from row p on, as far as the
+// factor is non-singular (a singular subset keeps them for its leading
+// rows, which a later proposal may reuse).
+template <int D>
+__device__ __forceinline__ double solve_from(Factor<D>& f, const double* __restrict__ c, const int* a, int p) {
+#pragma unroll
+    for (int j = 0; j < D; j++) {
+        if (j < p) continue;
+        if (!f.ok[j + 1]) break;
+        double v = c[a[j]];
+#pragma unroll
+        for (int k = 0; k < j; k++) v = v - f.L[j][k] * f.w[k];
+        f.w[j] = v / f.L[j][j];
+        f.ex[j + 1] = f.ex[j] + f.w[j] * f.w[j];
+    }
+    return f.ok[D] ? 1.0 - f.ex[D] : INFINITY;
+}
+
 template <int D>
 __device__ __forceinline__ void sort_rows(int* s) {
 #pragma unroll
@@ -236,7 +299,16 @@ __global__ __launch_bounds__(256) void k_sa_run(ctab<SaArgs> A, SaRun R) {
             }
         }
     }
-    double E = energy<D>(g.C, g.c, S, a);
+    // the factor of the current subset
+    Factor<D> f;
+#pragma unroll
+    for (int i = 0; i < D; i++)
+#pragma unroll
+        for (int j = 0; j <= i; j++) f.M[i][j] = g.C[(int64_t)a[i] * S + a[j]];
+    f.ok[0] = true;
+    f.ex[0] = 0.0;
+    factor_from<D>(f, 0);
+    double E = solve_from<D>(f, g.c, a, 0);
     double bE = E;
 #pragma unroll
     for (int j = 0; j < D; j++) bs[j] = a[j];
@@ -254,12 +326,21 @@ __global__ __launch_bounds__(256) void k_sa_run(ctab<SaArgs> A, SaRun R) {
         if (!in) {
 #pragma unroll
             for (int j = 0; j < D; j++) b[j] = j == p ? r : a[j];
-            const double En = energy<D>(g.C, g.c, S, b);
+            Factor<D> h = f;
+#pragma unroll
+            for (int j = 0; j < D; j++) {              // row / column p of the new subset
+                const double v = g.C[(int64_t)r * S + b[j]];
+                if (j <= p) h.M[p][j] = v;
+                if (j >= p) h.M[j][p] = v;
+            }
+            factor_from<D>(h, p);
+            const double En = solve_from<D>(h, g.c, b, p);
             bool acc = En <= E;
             if (!acc && En < INFINITY) acc = u < exp_neg((En - E) / T);
             if (acc) {
 #pragma unroll
                 for (int j = 0; j < D; j++) a[j] = b[j];
+                f = h;
                 E = En;
                 int sa[D];
 #pragma unroll

@@ -202,6 +202,33 @@ def large24():
                      n_resid=8, omp_D=6, planted=[t1, t2, t3, t4, t5])
 
 
+def subspace3000():
+    """A subspace shaped like the large workload's dimension-3 union, for
+    the annealing search: S = 3000 rows over n = 2000 samples, each the
+    product of two or three of 24 lognormal(0, 0.5) latent columns raised
+    to powers in {-2, -1, 1, 2} (so rows correlate as generated features
+    do); a planted 6-row model with coefficients +-U[0.5, 2] on
+    standardised rows, intercept 0.5, 1 % noise; candidate IDs are 3000
+    distinct values below 7e8.  D = 6 (exhaustive L0 would visit 1e18
+    subsets)."""
+    rng = np.random.default_rng(6)
+    n, S, p = 2000, 3000, 24
+    Z = rng.lognormal(0.0, 0.5, size=(p, n))
+    F = np.empty((S, n))
+    for i in range(S):
+        k = int(rng.integers(2, 4))
+        cols = rng.choice(p, size=k, replace=False)
+        pw = rng.choice([-2, -1, 1, 2], size=k)
+        F[i] = np.prod([Z[c] ** e for c, e in zip(cols, pw)], axis=0)
+    rows = rng.choice(S, size=6, replace=False)
+    coef = rng.uniform(0.5, 2.0, size=6) * rng.choice([-1.0, 1.0], size=6)
+    yc = 0.5 + sum(c * (F[r] - F[r].mean()) / F[r].std() for c, r in zip(coef, rows))
+    y = yc + _noise(rng, yc, 0.01)
+    ids = np.sort(rng.choice(700_000_000, size=S, replace=False)).astype(np.int64)
+    return {"name": "subspace3000", "F": F, "y": y, "ids": ids, "n": n, "S": S, "D": 6,
+            "planted_rows": sorted(int(r) for r in rows)}
+
+
 def random_small(seed, p=4, n=30, rung=2, T=1, units_B=0, lo=0.5, hi=2.0):
     """Small random problem for brute-force cross checks."""
     rng = np.random.default_rng(seed)

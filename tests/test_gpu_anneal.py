@@ -53,7 +53,12 @@ def _problem(seed, S, n, D, collinear=False):
     (40, 90, 1, 8, 500, 0.05, 0.99, 3, None, False),
     (31, 77, 8, 16, 1500, 0.02, 0.998, 4, None, True),
     (12, 40, 3, 5, 0, 0.01, 1.0, 5, (2, 0, 9), True),
-    (9, 30, 9 - 1, 4, 300, 0.0, 1.0, 6, None, False)])
+    (9, 30, 9 - 1, 4, 300, 0.0, 1.0, 6, None, False),
+    # singular starts: rows 2 and 9 are equal, rows 1, 3, 5 collinear
+    (14, 50, 4, 8, 800, 0.02, 0.999, 7, (0, 2, 9, 4), True),
+    (14, 50, 6, 8, 800, 0.02, 0.999, 8, (1, 3, 5, 2, 9, 7), True),
+    (120, 200, 6, 64, 1500, 0.01, 0.998, 9, None, True),
+    (60, 100, 7, 32, 1000, 0.02, 0.998, 10, (2, 9, 1, 3, 5, 11, 40), True)])
 def test_anneal_trajectory_equals_oracle(torch, ctx, oracle_mod, S, n, D, Q, K, T0, alpha, seed, init,
                                          collinear):
     O = oracle_mod
