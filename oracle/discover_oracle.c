@@ -1216,3 +1216,59 @@ int or_sa_run(int S, const double* C, const double* c, const int64_t* ids, int D
             w = q;
     return w;
 }
+
+/* ------------------------------------------------------------------------ */
+/* The constraint language (Design Philosophy and Constraints)               */
+/* ------------------------------------------------------------------------ */
+/* Rules that restrict the expressions allowed as descriptors (a reading of
+ * the paper's rules on variable combinations and functional forms, its
+ * complexity limits and the target-unit filter):
+ *   complexity    the number of operator nodes of the expression (a
+ *                 primary has 0, op(f) has 1 + c(f), op(f, g) has
+ *                 1 + c(f) + c(g)) is at most max_cplx (-1: no limit);
+ *   nesting       nest[o] bit c set: operator c may not be the top operator
+ *                 of a direct operand of operator o (e.g. exp of exp);
+ *   variables     forb[u] bit v set: primaries u and v (both < 64) may not
+ *                 appear together in one expression;
+ *   target unit   (target_on) the expression's unit vector equals tunit
+ *                 (scaled by 2^R as the unit vectors are).
+ * The first three are hereditary: an expression is allowed only if every
+ * sub-expression is.  Rules restrict which candidates can be selected; they
+ * do not change the search space, its unit-valid counts or the values of
+ * any candidate.  allowed[t] = 1 for an allowed record of an enumeration
+ * (records list their operands first); uout are or_units' vectors. */
+void or_rules(int64_t N, const int8_t* op, const int64_t* a, const int64_t* b, int max_cplx,
+              const uint32_t* nest, const uint64_t* forb, int target_on, int B, const int32_t* uout,
+              const uint8_t* legal, const int32_t* tunit, uint8_t* allowed) {
+    int32_t* cplx = (int32_t*)malloc(sizeof(int32_t) * (size_t)(N > 0 ? N : 1));
+    uint64_t* vars = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(N > 0 ? N : 1));
+    uint8_t* ok = (uint8_t*)malloc((size_t)(N > 0 ? N : 1));
+    for (int64_t t = 0; t < N; t++) {
+        if (op[t] == OP_NONE) {
+            cplx[t] = 0;
+            vars[t] = t < 64 ? (uint64_t)1 << t : 0;
+            ok[t] = 1;
+        } else {
+            const int64_t ia = a[t], ib = b[t];
+            cplx[t] = 1 + cplx[ia] + (ib >= 0 ? cplx[ib] : 0);
+            vars[t] = vars[ia] | (ib >= 0 ? vars[ib] : 0);
+            int good = ok[ia] && (ib < 0 || ok[ib]);
+            if (max_cplx >= 0 && cplx[t] > max_cplx) good = 0;
+            if (op[ia] != OP_NONE && (nest[op[t]] >> op[ia] & 1u)) good = 0;
+            if (ib >= 0 && op[ib] != OP_NONE && (nest[op[t]] >> op[ib] & 1u)) good = 0;
+            if (ib >= 0)
+                for (int u = 0; u < 64; u++)
+                    if ((vars[ia] >> u & 1u) && (forb[u] & vars[ib])) good = 0;
+            ok[t] = (uint8_t)good;
+        }
+        int al = ok[t];
+        if (al && target_on) {
+            if (!legal[t]) al = 0;
+            for (int k = 0; k < B && al; k++) al = uout[t * B + k] == tunit[k];
+        }
+        allowed[t] = (uint8_t)al;
+    }
+    free(cplx);
+    free(vars);
+    free(ok);
+}

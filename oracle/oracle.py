@@ -119,6 +119,8 @@ def lib():
         L.or_sa_run.restype = C.c_int
         L.or_sa_run.argtypes = [C.c_int, P, P, P, C.c_int, C.c_int, C.c_int64, C.c_double,
                                 C.c_double, C.c_uint64, P, P, P]
+        L.or_rules.restype = None
+        L.or_rules.argtypes = [C.c_int64, P, P, P, C.c_int, P, P, C.c_int, C.c_int, P, P, P, P]
         L.or_max_threads.restype = C.c_int
         L.or_set_threads.restype = None
         L.or_set_threads.argtypes = [C.c_int]
@@ -206,6 +208,35 @@ class Space:
         lib().or_units(self.p, B, _p(uin), self.R, self.N, _p(op), _p(a), _p(b),
                        _p(uo), _p(legal))
         return uo[:, :B], legal.astype(bool)
+
+    def rules_allowed(self, units, rules):
+        """Mask of the candidates the constraint rules allow (or_rules):
+        rules = {max_complexity: int, forbid_nest: {op: [ops]}, forbid_pairs:
+        [[i, j], ...] (primaries < 64), target_units: [B] exponents or None}."""
+        rung, op, a, b = self.enumerate()
+        B = 0 if units is None else units.shape[1]
+        uo = np.zeros((self.N, max(B, 1)), np.int32)
+        legal = np.zeros(self.N, np.uint8)
+        uin = None if units is None else np.ascontiguousarray(units, np.int32)
+        lib().or_units(self.p, B, _p(uin), self.R, self.N, _p(op), _p(a), _p(b), _p(uo), _p(legal))
+        nest = np.zeros(10, np.uint32)
+        for o, cs in (rules.get("forbid_nest") or {}).items():
+            for c_ in cs:
+                nest[OPS.index(o)] |= np.uint32(1 << OPS.index(c_))
+        forb = np.zeros(64, np.uint64)
+        for u, v in rules.get("forbid_pairs") or ():
+            forb[u] |= np.uint64(1 << v)
+            forb[v] |= np.uint64(1 << u)
+        tu = rules.get("target_units")
+        on = tu is not None
+        tunit = np.zeros(max(B, 1), np.int32)
+        if on:
+            tunit[:B] = np.asarray(tu, np.int64) * (1 << self.R)
+        allowed = np.zeros(self.N, np.uint8)
+        lib().or_rules(self.N, _p(op), _p(a), _p(b), int(rules.get("max_complexity", -1)), _p(nest),
+                       _p(forb), 1 if on else 0, B, _p(np.ascontiguousarray(uo[:, :max(B, 1)])),
+                       _p(legal), _p(tunit), _p(allowed))
+        return allowed.astype(bool)
 
     def expr(self, cid):
         """Readable expression of an ID (primaries named x0, x1, ...)."""
@@ -410,13 +441,17 @@ def _scan(score, order, k, excl, dedup, value_fn):
     return reps[o], sc[o], {"groups": len(heads), "merged": n_merged}, stopped
 
 
-def sis(space, X, units, targets, k, exclude=(), mode="per_target", dedup=True):
+def sis(space, X, units, targets, k, exclude=(), mode="per_target", dedup=True, allowed=None):
     """Screen every candidate against the targets and select the top-k
     (per target, or one list scored by the maximum over targets).  Returns
     (one (ids, scores, record) per list, status, number of valid
     candidates); status is the per-candidate ST_* array, or, when the space
-    was streamed, the count of each ST_* code."""
+    was streamed, the count of each ST_* code.  allowed: a boolean mask of
+    the candidates the rules allow (Space.rules_allowed), or None."""
     sc, nvalid, status, counts = screen_scores(space, X, targets, units, mode)
+    if allowed is not None:
+        sc = sc.copy()
+        sc[:, ~np.asarray(allowed, bool)] = np.nan   # never selected; counts unchanged
     cache = {}
 
     def value_fn(cid):
