@@ -284,6 +284,36 @@ discover_status discover_omp(discover_ctx* ctx, const discover_l0_problem* probs
                              int32_t* out_active, double* out_coef, double* out_rmse,
                              double* out_resid, int64_t ldr, void* stream);
 
+/* Constraint rules on the expressions that may be selected (Design
+ * Philosophy and Constraints: rules on variable combinations and functional
+ * forms, complexity limits, a target-unit filter).  The first three are
+ * hereditary: an expression is allowed only if every sub-expression is.
+ *   max_complexity  operator nodes of the expression at most this (a primary
+ *                   has 0, op(f) 1 + c(f), op(f, g) 1 + c(f) + c(g)); -1: none
+ *   forbid_nest[o]  bit c (DISCOVER_OP_* order): operator c may not be the top
+ *                   operator of a direct operand of operator o (e.g. exp(exp(f)))
+ *   forbid_pairs    host [n_forbid_pairs][2]: primaries (index < 64) that may
+ *                   not appear together in one expression
+ *   target_unit     1: the expression's unit vector must equal target_units
+ *                   (exponents over each problem's B base units)
+ * Rules restrict selection only: candidates are still generated, screened
+ * and counted as before (stats are unchanged), and an operand feature stays
+ * usable inside larger expressions subject to the hereditary rules. */
+typedef struct {
+    int32_t max_complexity;
+    uint32_t forbid_nest[10];
+    int32_t n_forbid_pairs;
+    const int32_t* forbid_pairs;
+    int32_t target_unit;
+    int32_t target_units[8];
+} discover_rules;
+
+/* Rules for every later screening call on this context (copied; NULL
+ * clears them).  Waits for the device; graphs captured and selection sizes
+ * memoised before are discarded.
+ * Errors: E_ARG, E_HIP. */
+discover_status discover_set_rules(discover_ctx* ctx, const discover_rules* rules);
+
 /* Parameters of the annealing search (discover_l0_anneal). */
 typedef struct {
     int32_t chains;           /* independent chains per problem, 1..2^20 (thousands fill the GPU) */

@@ -70,12 +70,18 @@ class AnnealParams(C.Structure):
                 ("T0", C.c_double), ("alpha", C.c_double), ("seed", C.c_uint64)]
 
 
+class Rules(C.Structure):
+    _fields_ = [("max_complexity", C.c_int32), ("forbid_nest", C.c_uint32 * 10),
+                ("n_forbid_pairs", C.c_int32), ("forbid_pairs", C.c_void_p),
+                ("target_unit", C.c_int32), ("target_units", C.c_int32 * 8)]
+
+
 # Every symbol include/discover.h declares.
 SYMBOLS = ("discover_create", "discover_destroy", "discover_last_error",
            "discover_generate_screen", "discover_l0_fit", "discover_omp", "discover_count",
            "discover_decode", "discover_set_timing", "discover_timing", "discover_reset_timing",
            "discover_sisso_batch", "discover_set_graph_timing", "discover_set_fixup_capacity",
-           "discover_reserve", "discover_omp_noalloc", "discover_l0_anneal")
+           "discover_reserve", "discover_omp_noalloc", "discover_l0_anneal", "discover_set_rules")
 
 _lib = None
 
@@ -116,6 +122,7 @@ def lib():
                                            C.c_int32, P, P, P, C.POINTER(C.c_int32), P]
         L.discover_set_graph_timing.argtypes = [P, C.c_char_p]
         L.discover_set_fixup_capacity.argtypes = [P, C.c_int64]
+        L.discover_set_rules.argtypes = [P, C.POINTER(Rules)]
         _lib = L
     return _lib
 
@@ -210,6 +217,33 @@ class Context:
     def set_fixup_capacity(self, entries):
         """Initial entries of the screening's exact fix-up lists."""
         _check(lib().discover_set_fixup_capacity(self.h, int(entries)))
+
+    def set_rules(self, rules=None):
+        """Selection rules of the following screening calls (None clears):
+        {max_complexity: int (-1 none), forbid_nest: {op: [ops]} (the ops
+        that may not be the top operator of op's operands), forbid_pairs:
+        [[i, j], ...] (primary indices < 64 that may not appear together),
+        target_units: [B] exponents over the problems' base units, or None}."""
+        if rules is None:
+            _check(lib().discover_set_rules(self.h, None))
+            return
+        r = Rules()
+        r.max_complexity = int(rules.get("max_complexity", -1))
+        for o, cs in (rules.get("forbid_nest") or {}).items():
+            for c in cs:
+                r.forbid_nest[OPS.index(o)] |= OP_BIT[c]
+        pairs = [int(v) for pr in (rules.get("forbid_pairs") or ()) for v in pr]
+        arr = (C.c_int32 * max(len(pairs), 1))(*pairs)
+        r.n_forbid_pairs = len(pairs) // 2
+        r.forbid_pairs = C.cast(arr, C.c_void_p) if pairs else None
+        tu = rules.get("target_units")
+        if tu is not None:
+            if len(tu) > 8:
+                raise ValueError("target_units: at most 8 base units")
+            r.target_unit = 1
+            for i, v in enumerate(tu):
+                r.target_units[i] = int(v)
+        _check(lib().discover_set_rules(self.h, C.byref(r)))
 
     def timing(self, kernel):
         n = C.c_int64()

@@ -114,6 +114,36 @@ extern "C" discover_status discover_set_fixup_capacity(discover_ctx* ctx, int64_
     });
 }
 
+extern "C" discover_status discover_set_rules(discover_ctx* ctx, const discover_rules* rules) {
+    using namespace dsc;
+    return guarded([&] {
+        DSC_REQUIRE(ctx, "ctx is NULL");
+        if (rules) {
+            DSC_REQUIRE(rules->max_complexity >= -1, "max_complexity %d < -1", rules->max_complexity);
+            for (int o = 0; o < 10; o++)
+                DSC_REQUIRE((rules->forbid_nest[o] & ~DISCOVER_OPS_ALL) == 0, "forbid_nest[%d]", o);
+            DSC_REQUIRE(rules->n_forbid_pairs >= 0 && (rules->n_forbid_pairs == 0 || rules->forbid_pairs),
+                        "forbid_pairs");
+            for (int i = 0; i < 2 * rules->n_forbid_pairs; i++)
+                DSC_REQUIRE(rules->forbid_pairs[i] >= 0 && rules->forbid_pairs[i] < 64,
+                            "forbid_pairs: primary %d outside 0..63", rules->forbid_pairs[i]);
+            DSC_REQUIRE(rules->target_unit == 0 || rules->target_unit == 1, "target_unit");
+            ctx->rules = *rules;
+            ctx->rule_pairs.assign(rules->forbid_pairs, rules->forbid_pairs + 2 * rules->n_forbid_pairs);
+            ctx->rules.forbid_pairs = nullptr;
+            ctx->has_rules = true;
+        } else {
+            ctx->has_rules = false;
+            ctx->rule_pairs.clear();
+        }
+        // captured graphs and the memoised selection sizes belong to the old rules
+        DSC_HIP(hipSetDevice(ctx->device));
+        DSC_HIP(hipDeviceSynchronize());
+        ctx->batches.clear();
+        ctx->generation++;
+    });
+}
+
 extern "C" discover_status discover_set_timing(discover_ctx* ctx, int32_t enable) {
     using namespace dsc;
     return guarded([&] {

@@ -144,6 +144,10 @@ struct discover_ctx {
     // again.
     int64_t fix_cap_min = (int64_t)1 << 22;
     hipStream_t side = nullptr;            // private stream for uploads during capture
+    // Selection rules (discover_set_rules): the copied parameters and pairs.
+    bool has_rules = false;
+    discover_rules rules{};
+    std::vector<int32_t> rule_pairs;
 
     // Grow-only named device buffer of at least `bytes` bytes.
     void* raw(const std::string& name, size_t bytes) {

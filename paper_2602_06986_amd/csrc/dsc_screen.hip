@@ -1330,6 +1330,120 @@ struct PoolVals {
     double *mean, *sxx;
 };
 
+// ------------------------------------------------------ selection rules
+// Per operand feature (compact index): its primaries (bits < 64), operator
+// count, top operator and whether it and all its sub-expressions pass the
+// hereditary rules.
+struct RuleFeat {
+    uint64_t vars;
+    int32_t cplx;
+    int8_t top;
+    uint8_t ok;
+    int16_t pad;
+};
+
+struct RuleTab {
+    const RuleFeat* feat;
+    const int32_t* unit;      // [Mc][B] unit vectors (scaled as the space's), for the target filter
+    int B, max_cplx, target;
+    uint32_t nest[10];
+    int32_t tunit[8];
+    uint64_t forb[64];
+};
+
+__device__ __forceinline__ bool pairs_forbidden(const RuleTab& R, uint64_t A, uint64_t B) {
+    while (A) {
+        const int u = __ffsll((long long)A) - 1;
+        A &= A - 1;
+        if (R.forb[u] & B) return true;
+    }
+    return false;
+}
+
+__device__ __forceinline__ bool nest_forbidden(const RuleTab& R, int op, int child_top) {
+    return child_top != OP_NONE && ((R.nest[op] >> child_top) & 1u);
+}
+
+// Unit vector of op over operand vectors (the operator's rule holds: the
+// candidate is unit-legal).
+__device__ __forceinline__ void unit_apply(int op, int B, const int32_t* ua, const int32_t* ub, int32_t* out) {
+    for (int k = 0; k < B; k++) {
+        int32_t v = 0;
+        switch (op) {
+        case OP_EXP: case OP_LOG: v = 0; break;
+        case OP_SQRT: v = ua[k] / 2; break;
+        case OP_SQ: v = 2 * ua[k]; break;
+        case OP_INV: v = -ua[k]; break;
+        case OP_ADD: case OP_SUB: v = ua[k]; break;
+        case OP_MUL: v = ua[k] + ub[k]; break;
+        case OP_DIV: v = ua[k] - ub[k]; break;
+        default: v = ub[k] - ua[k]; break;       // rdiv
+        }
+        out[k] = v;
+    }
+}
+
+// Whether the rules allow candidate c (one lane's work; c decoded by
+// cand_of_id, so its operands are operand features or, for kind 3, a
+// rung-2 feature op2(cc, cd) over operand features).
+__device__ __forceinline__ bool rules_pass(const RuleTab& R, const Cand& c) {
+    const RuleFeat* F = R.feat;
+    int32_t u[8], ug[8];
+    int cplx;
+    if (c.kind == 0) {
+        const RuleFeat& f = F[c.ca];
+        if (!f.ok) return false;
+        if (R.target)
+            for (int k = 0; k < R.B; k++)
+                if (R.unit[(int64_t)c.ca * R.B + k] != R.tunit[k]) return false;
+        return true;
+    }
+    const RuleFeat& fa = F[c.ca];
+    if (!fa.ok || nest_forbidden(R, c.op, fa.top)) return false;
+    const int32_t* ua = R.unit ? R.unit + (int64_t)c.ca * R.B : nullptr;
+    if (c.kind == 1) {
+        cplx = 1 + fa.cplx;
+        if (R.target) unit_apply(c.op, R.B, ua, nullptr, u);
+    } else {
+        uint64_t vb;
+        int cb, topb;
+        const int32_t* ubp = ug;
+        if (c.kind == 2) {
+            const RuleFeat& fb = F[c.cb];
+            if (!fb.ok) return false;
+            vb = fb.vars;
+            cb = fb.cplx;
+            topb = fb.top;
+            if (R.unit) ubp = R.unit + (int64_t)c.cb * R.B;
+        } else {                                  // the rung-2 operand op2(cc, cd)
+            const RuleFeat& f1 = F[c.cc];
+            if (!f1.ok || nest_forbidden(R, c.op2, f1.top)) return false;
+            vb = f1.vars;
+            cb = 1 + f1.cplx;
+            if (c.cd >= 0) {
+                const RuleFeat& f2 = F[c.cd];
+                if (!f2.ok || nest_forbidden(R, c.op2, f2.top) || pairs_forbidden(R, f1.vars, f2.vars))
+                    return false;
+                vb |= f2.vars;
+                cb += f2.cplx;
+            }
+            if (R.max_cplx >= 0 && cb > R.max_cplx) return false;
+            topb = c.op2;
+            if (R.target)
+                unit_apply(c.op2, R.B, R.unit + (int64_t)c.cc * R.B,
+                           c.cd >= 0 ? R.unit + (int64_t)c.cd * R.B : nullptr, ug);
+        }
+        if (nest_forbidden(R, c.op, topb) || pairs_forbidden(R, fa.vars, vb)) return false;
+        cplx = 1 + fa.cplx + cb;
+        if (R.target) unit_apply(c.op, R.B, ua, ubp, u);
+    }
+    if (R.max_cplx >= 0 && cplx > R.max_cplx) return false;
+    if (R.target)
+        for (int k = 0; k < R.B; k++)
+            if (u[k] != R.tunit[k]) return false;
+    return true;
+}
+
 template <int TMAX>
 __device__ __forceinline__ void d_rescore(const int64_t* __restrict__ pool,
                                                  const unsigned long long* __restrict__ Pp, int64_t cap,
@@ -1344,13 +1458,15 @@ __device__ __forceinline__ void d_rescore(const int64_t* __restrict__ pool,
                                                  double* __restrict__ perr,
                                                  int32_t* __restrict__ rank,
                                                  int32_t* __restrict__ order,
-                                                 const PoolVals pvs) {
+                                                 const PoolVals pvs, const RuleTab* __restrict__ rules) {
     const int64_t P = min((int64_t)*Pp, cap);
     const int lane = threadIdx.x & 63;
     for (int64_t w = (int64_t)blockIdx.x * 4 + wave_id(); w < P; w += (int64_t)gridDim.x * 4) {
     const int64_t id = pool[w];
     Cand c;
     bool ok = cand_of_id(ev, id, c);
+    // a candidate the rules do not allow keeps its values but is never selected
+    const bool allowed = !ok || !rules || rules_pass(*rules, c);
     double r[TMAX];
     const bool keep = w < pvs.cap;
     double m = 0.0, sxx = 0.0;
@@ -1372,7 +1488,7 @@ __device__ __forceinline__ void d_rescore(const int64_t* __restrict__ pool,
             } else {
                 s = fabs(r[tlist]);
             }
-            if (!(s > 0.0)) s = -1.0;
+            if (!(s > 0.0) || !allowed) s = -1.0;
         }
         ps[w] = s;
         pex[w] = (uint8_t)ex;
@@ -2081,6 +2197,7 @@ struct SelArgs {
     int64_t* res;
     PoolVals pvs;             // stored values of the first pvs.cap pool entries
     int64_t* vrow;            // per selected rank: address of its stored value row, 0 for none
+    const RuleTab* rules;     // selection rules, or NULL
 };
 
 // grid (blocks, lists) for the streaming kernels, (lists) for the one-block ones
@@ -2094,7 +2211,8 @@ __global__ __launch_bounds__(256) void k_rescore(ctab<SelArgs> A) {
     const SelArgs& a = tab(A, blockIdx.y);
     DSC_GLOBAL(a.sc); DSC_GLOBAL(a.sel); DSC_GLOBAL(a.st); DSC_GLOBAL(a.pool); DSC_GLOBAL(a.cnt); DSC_GLOBAL(a.ev.raw2c); DSC_GLOBAL(a.ev.valid); DSC_GLOBAL(a.o.Vf); DSC_GLOBAL(a.o.Rf); DSC_GLOBAL(a.Yc); DSC_GLOBAL(a.syy); DSC_GLOBAL(a.ps); DSC_GLOBAL(a.pex); DSC_GLOBAL(a.maxerr); DSC_GLOBAL(a.order); DSC_GLOBAL(a.lo); DSC_GLOBAL(a.wc); DSC_GLOBAL(a.off); DSC_GLOBAL(a.flag); DSC_GLOBAL(a.parent); DSC_GLOBAL(a.blk); DSC_GLOBAL(a.repid); DSC_GLOBAL(a.reppos); DSC_GLOBAL(a.headpos); DSC_GLOBAL(a.out_ids); DSC_GLOBAL(a.out_sc); DSC_GLOBAL(a.res);
     d_rescore<DISCOVER_MAX_TARGETS>(a.pool, a.cnt, a.cap, a.ev, a.o, a.n, a.T, a.mode, a.t, a.Yc, a.syy,
-                                    a.excl, a.n_excl, a.ps, a.pex, a.sc, a.perr, a.rank, a.order, a.pvs);
+                                    a.excl, a.n_excl, a.ps, a.pex, a.sc, a.perr, a.rank, a.order, a.pvs,
+                                    a.rules);
 }
 
 // grid (i tiles, j chunks, lists)
@@ -2975,6 +3093,58 @@ static char* sel_layout(discover_ctx* ctx, int k, const std::vector<ListState>& 
     return (char*)ctx->raw("sel_arena" + ctx->tag, ar.total);
 }
 
+// The rule table of one problem (NULL without rules): the operand
+// features' metadata from the plan, uploaded with the rules.
+static const RuleTab* rule_table(discover_ctx* ctx, const Problem& P, int b, hipStream_t st) {
+    if (!ctx->has_rules) return nullptr;
+    const Space& sp = P.plan->sp;
+    const discover_rules& R = ctx->rules;
+    const int Mc = sp.Mc(), B = sp.B;
+    RuleTab t{};
+    for (int i = 0; i + 1 < (int)ctx->rule_pairs.size(); i += 2) {
+        const int u = ctx->rule_pairs[i], v = ctx->rule_pairs[i + 1];
+        t.forb[u] |= 1ull << v;
+        t.forb[v] |= 1ull << u;
+    }
+    for (int o = 0; o < 10; o++) t.nest[o] = R.forbid_nest[o];
+    t.max_cplx = R.max_complexity;
+    t.B = B;
+    t.target = R.target_unit && B > 0 ? 1 : 0;
+    for (int k = 0; k < B && k < 8; k++) t.tunit[k] = R.target_units[k] * (1 << sp.d.R);
+    std::vector<RuleFeat> f(Mc);
+    auto forbidden = [&](uint64_t A, uint64_t Bm) {
+        for (int u = 0; u < 64; u++)
+            if ((A >> u & 1ull) && (t.forb[u] & Bm)) return true;
+        return false;
+    };
+    for (int c = 0; c < Mc; c++) {
+        RuleFeat& x = f[c];
+        const int op = sp.mat_op[c];
+        if (op == OP_NONE) {
+            const int64_t prim = sp.mat_raw[c];
+            x.vars = prim < 64 ? 1ull << prim : 0;
+            x.cplx = 0;
+            x.top = (int8_t)OP_NONE;
+            x.ok = 1;
+            continue;
+        }
+        const int a = sp.mat_a[c], bb = sp.mat_b[c];
+        x.cplx = 1 + f[a].cplx + (bb >= 0 ? f[bb].cplx : 0);
+        x.vars = f[a].vars | (bb >= 0 ? f[bb].vars : 0);
+        x.top = (int8_t)op;
+        bool good = f[a].ok && (bb < 0 || f[bb].ok);
+        if (R.max_complexity >= 0 && x.cplx > R.max_complexity) good = false;
+        if (f[a].top != OP_NONE && (R.forbid_nest[op] >> f[a].top & 1u)) good = false;
+        if (bb >= 0 && f[bb].top != OP_NONE && (R.forbid_nest[op] >> f[bb].top & 1u)) good = false;
+        if (bb >= 0 && forbidden(f[a].vars, f[bb].vars)) good = false;
+        x.ok = good ? 1 : 0;
+    }
+    const std::string sfx = std::to_string(b);
+    t.feat = ctx->upload("sel_rule_feat" + sfx, f, st);
+    t.unit = t.target ? ctx->upload("sel_rule_unit" + sfx, sp.mat_unit, st) : nullptr;
+    return (const RuleTab*)ctx->upload("sel_rule_tab" + sfx, &t, sizeof t, st);
+}
+
 static void select_round(discover_ctx* ctx, const discover_problem* probs,
                          const discover_screen_params& prm, std::vector<Problem>& PS,
                          const std::vector<ListState>& LS, const std::vector<int>& act,
@@ -2991,6 +3161,7 @@ static void select_round(discover_ctx* ctx, const discover_problem* probs,
     std::vector<int64_t> vbase(PS.size() + 1, 0);              // value-row addresses, laid out as the IDs
     for (size_t b = 0; b < PS.size(); b++) vbase[b + 1] = vbase[b] + (int64_t)PS[b].Tl * k;
     int64_t* vrow = ctx->buf<int64_t>("scr_vrow" + ctx->tag, (size_t)vbase.back());
+    std::map<int, const RuleTab*> rtab;      // one rule table per problem
     for (int q = 0; q < nl; q++) {
         const ListState& L = LS[act[q]];
         const Problem& P = PS[L.b];
@@ -3022,6 +3193,9 @@ static void select_round(discover_ctx* ctx, const discover_problem* probs,
         a.k = k; a.dedup = prm.dedup;
         a.Yc = P.Yc; a.syy = P.syy;
         a.excl = pb.exclude; a.n_excl = pb.exclude ? pb.n_exclude : 0;
+        auto rt = rtab.find(L.b);
+        if (rt == rtab.end()) rt = rtab.emplace(L.b, rule_table(ctx, P, L.b, st)).first;
+        a.rules = rt->second;
         a.out_ids = outs[L.b].ids + (int64_t)L.t * k;
         a.out_sc = outs[L.b].sc + (int64_t)L.t * k;
         a.vrow = vrow + vbase[L.b] + (int64_t)L.t * k;
