@@ -364,6 +364,60 @@ discover_status discover_l0_anneal(discover_ctx* ctx, const discover_l0_problem*
                                    double* out_chain_energy, double* out_resid, int64_t ldr,
                                    void* stream);
 
+/* Limits of the branch-and-bound search (discover_l0_bnb). */
+typedef struct {
+    int64_t max_nodes;        /* prefixes expanded before the search stops with E_CAPACITY; 0: no limit */
+    int64_t reserved;         /* 0 */
+} discover_bnb_params;
+
+/* What one problem's branch-and-bound search did.  The counts depend on the
+ * order in which the GPU happened to visit the tree; the result does not. */
+typedef struct {
+    int64_t n_subsets;        /* C(S, D) */
+    int64_t n_nodes;          /* prefixes (partial subsets) expanded */
+    int64_t n_bounds;         /* bound evaluations */
+    int64_t n_leaves;         /* D-subsets whose explained fraction was computed */
+    int64_t n_refit;          /* subsets refitted by Householder QR */
+    int32_t m0;               /* trailing rows over which the bound is trusted (see below) */
+    int32_t status;           /* DISCOVER_OK, E_CAPACITY (max_nodes reached), E_NUMERIC */
+} discover_bnb_stats;
+
+/* Exact L0 (Eq. (1), Core Optimization Objective, with an intercept) by
+ * branch and bound on the correlation matrix, the exact alternative to
+ * enumeration the paper names beside the stochastic searches (Software
+ * Description): the same problem and result as discover_l0_fit (singular
+ * subsets skipped, the band within 1e-7 of the m-th best refitted by QR,
+ * ties within 1e-11 ||y - mean||^2 to the smallest sorted ID tuple) for D
+ * up to 8, without visiting every subset.
+ *
+ * Subsets are grown row by row in ascending row order.  A prefix P whose
+ * next row is j can only be completed from rows >= j, and the explained
+ * fraction never falls when rows are added, so R^2(P + rows >= j) bounds
+ * every subset below that branch; a branch whose bound is below the m-th
+ * best fraction found so far (less a margin of 1e-6 + 1e-7) is cut, and
+ * since the bound falls as j grows, so are all later siblings.  The bounds
+ * come from one Cholesky factor of the correlation matrix in reverse row
+ * order; once that factor meets a pivot <= 1e-6 (rows nearly dependent on
+ * the rows after them), branches needing more of it are not cut (m0 in
+ * the stats: the number of trailing rows it covers).  The search is exact;
+ * how much of the tree it skips depends on the data (strongly planted
+ * models: almost all of it; nearly collinear subspaces: less).
+ *
+ *   D, m           1..DISCOVER_MAX_D, 1..64
+ *   S              D..2048
+ *   prm            limits, or NULL for none
+ *   out_*          as discover_l0_fit
+ *   out_stats      host [n_problems], or NULL
+ * The call waits for the stream (the host steers the search) and cannot be
+ * captured.
+ * Errors: E_ARG, E_CAPACITY (max_nodes), E_NUMERIC (constant y, or no
+ * non-singular subset), E_NOMEM, E_HIP. */
+discover_status discover_l0_bnb(discover_ctx* ctx, const discover_l0_problem* probs,
+                                int32_t n_problems, int32_t D, int32_t m,
+                                const discover_bnb_params* prm, int32_t* out_subsets,
+                                double* out_rmse, double* out_coef, double* out_resid, int64_t ldr,
+                                discover_bnb_stats* out_stats, void* stream);
+
 /* discover_omp for callers that cannot allocate device memory (code under
  * graph capture, tight serving loops, harnesses that forbid allocation):
  * the same arguments, kernels and results, with the work buffers taken

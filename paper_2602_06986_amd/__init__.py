@@ -70,6 +70,18 @@ class AnnealParams(C.Structure):
                 ("T0", C.c_double), ("alpha", C.c_double), ("seed", C.c_uint64)]
 
 
+class BnbParams(C.Structure):
+    _fields_ = [("max_nodes", C.c_int64), ("reserved", C.c_int64)]
+
+
+class BnbStats(C.Structure):
+    _fields_ = [("n_subsets", C.c_int64), ("n_nodes", C.c_int64), ("n_bounds", C.c_int64),
+                ("n_leaves", C.c_int64), ("n_refit", C.c_int64), ("m0", C.c_int32), ("status", C.c_int32)]
+
+    def asdict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class Rules(C.Structure):
     _fields_ = [("max_complexity", C.c_int32), ("forbid_nest", C.c_uint32 * 10),
                 ("n_forbid_pairs", C.c_int32), ("forbid_pairs", C.c_void_p),
@@ -81,7 +93,7 @@ SYMBOLS = ("discover_create", "discover_destroy", "discover_last_error",
            "discover_generate_screen", "discover_l0_fit", "discover_omp", "discover_count",
            "discover_decode", "discover_set_timing", "discover_timing", "discover_reset_timing",
            "discover_sisso_batch", "discover_set_graph_timing", "discover_set_fixup_capacity",
-           "discover_reserve", "discover_omp_noalloc", "discover_l0_anneal", "discover_set_rules")
+           "discover_reserve", "discover_omp_noalloc", "discover_l0_anneal", "discover_set_rules", "discover_l0_bnb")
 
 _lib = None
 
@@ -110,6 +122,8 @@ def lib():
         L.discover_omp_noalloc.argtypes = L.discover_omp.argtypes
         L.discover_l0_anneal.argtypes = [P, C.POINTER(L0Problem), C.c_int32, C.c_int32,
                                          C.POINTER(AnnealParams), P, P, P, P, P, P, P, P, C.c_int64, P]
+        L.discover_l0_bnb.argtypes = [P, C.POINTER(L0Problem), C.c_int32, C.c_int32, C.c_int32,
+                                      C.POINTER(BnbParams), P, P, P, P, C.c_int64, P, P]
         L.discover_count.argtypes = [C.c_int32, C.POINTER(ScreenParams)]
         L.discover_count.restype = C.c_int64
         L.discover_decode.argtypes = [C.c_int32, C.POINTER(ScreenParams), C.c_int64, C.c_char_p,
@@ -371,6 +385,39 @@ class Context:
         (subsets [m][D] rows, rmse [m], coef [m][D+1], resid [m][n], stats)."""
         ((sub, rmse, coef, res, st),) = self.l0_fit_batch([F], [ids], [y], D, m, resid, device_stats)
         return sub, rmse, coef, res, st
+
+    def l0_bnb_batch(self, Fs, idss, ys, D, m=1, resid=True, max_nodes=0):
+        """Exact L0 by branch and bound (discover_l0_bnb) over many subspaces:
+        Fs[b] [S_b][n_b], idss[b] [S_b] int64, ys[b] [n_b] (CUDA).  Returns per
+        dataset (subsets [m][D] rows, rmse [m], coef [m][D+1], resid [m][n] or
+        None, stats dict)."""
+        torch = self.torch
+        nb = len(Fs)
+        Fs = [f.contiguous() for f in Fs]
+        idss = [i.contiguous() for i in idss]
+        ys = [y.contiguous() for y in ys]
+        dev = Fs[0].device
+        nmax = max(f.shape[1] for f in Fs)
+        sub = torch.empty((nb, m, D), dtype=torch.int32, device=dev)
+        rmse = torch.empty((nb, m), dtype=torch.float64, device=dev)
+        coef = torch.empty((nb, m, D + 1), dtype=torch.float64, device=dev)
+        res = torch.empty((nb, m, nmax), dtype=torch.float64, device=dev) if resid else None
+        pbs = (L0Problem * nb)()
+        for b in range(nb):
+            S, n = Fs[b].shape
+            pbs[b].n, pbs[b].S, pbs[b].F, pbs[b].ldf = n, S, Fs[b].data_ptr(), n
+            pbs[b].ids, pbs[b].y = idss[b].data_ptr(), ys[b].data_ptr()
+        st = (BnbStats * nb)()
+        prm = BnbParams(int(max_nodes), 0)
+        _check(lib().discover_l0_bnb(self.h, pbs, nb, D, m, C.byref(prm), sub.data_ptr(), rmse.data_ptr(),
+                                     coef.data_ptr(), res.data_ptr() if res is not None else None, nmax, st,
+                                     _stream_handle(torch, dev)))
+        return [(sub[b], rmse[b], coef[b], res[b, :, :Fs[b].shape[1]] if res is not None else None,
+                 st[b].asdict()) for b in range(nb)]
+
+    def l0_bnb(self, F, ids, y, D, m=1, resid=True, max_nodes=0):
+        """l0_bnb_batch for one subspace."""
+        return self.l0_bnb_batch([F], [ids], [y], D, m, resid, max_nodes)[0]
 
     def anneal_batch(self, Fs, idss, ys, D, chains=4096, steps=10000, T0=0.01, alpha=0.9995, seed=0,
                      inits=None, chain_results=False, resid=False):

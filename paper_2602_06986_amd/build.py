@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdiscover.so")
 SOURCES = ["dsc_abi.cpp", "dsc_space.cpp", "dsc_screen.hip", "dsc_r3.hip", "dsc_l0.hip", "dsc_batch.hip",
-           "dsc_noalloc.hip", "dsc_anneal.hip"]
+           "dsc_noalloc.hip", "dsc_anneal.hip", "dsc_bnb.hip"]
 ARCH = os.environ.get("DISCOVER_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -156,6 +156,27 @@ size_t omp_scratch_bytes(const discover_l0_problem* probs, int nb, int D_max, bo
 void fit_rows(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D, const int32_t* rows,
               int64_t rows_ld, double* coef, int64_t coef_ld, double* rmse, double* resid, int64_t ldr,
               hipStream_t st);
+// Explained fractions (Eq. (1) through the normal equations) share these
+// with every L0 search: the singular-pivot rule, the band of the QR refit
+// and the RSS tie tolerance.
+constexpr double PIV_TOL = 1e-10;     // normalized Cholesky pivot at/below which a subset is singular
+constexpr double GRAM_DELTA = 1e-7;   // band width in explained fraction
+constexpr double TAU_TIE = 1e-11;     // RSS tie tolerance relative to ||y - mean||^2
+
+// Standardised rows and the (S + 1) x (S + 1) correlation matrix of one L0
+// problem (row S: y), G[a * ldg + b]; yy = ||y - mean||^2.  Buffers are
+// named from `name`.
+struct GramOut {
+    double* G;
+    int ldg;
+    double* yy;
+    double* dg;               // G's diagonal, contiguous
+};
+GramOut l0_gram_one(discover_ctx* ctx, const discover_l0_problem& pb, const std::string& name,
+                    hipStream_t st);
+// QR residual sum of squares of `count` D-subsets subs[count][D] (device).
+void refit_list(discover_ctx* ctx, const discover_l0_problem& pb, int D, const int32_t* subs, int64_t count,
+                double* rss, hipStream_t st);
 void validate_omp(const discover_l0_problem* probs, int32_t n_problems, int32_t D_max,
                   const int32_t* init_active, int32_t n_init, const int32_t* out_active,
                   const double* out_coef, const double* out_rmse, const double* out_resid, int64_t ldr);

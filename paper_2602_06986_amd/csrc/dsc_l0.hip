@@ -20,10 +20,7 @@
 
 namespace dsc {
 
-constexpr double PIV_TOL = 1e-10;     // normalized Cholesky pivot at/below which a subset is singular
-constexpr double GRAM_DELTA = 1e-7;   // band width in explained fraction
 constexpr double SW3_RCP_DELTA = 4.76837158203125e-7;  // 2^-21: D = 3 sweep values use a bare rcp
-constexpr double TAU_TIE = 1e-11;     // RSS tie tolerance relative to ||y - mean||^2
 
 // ------------------------------------------------------------------ prep
 // One wave per row (rows 0..S-1 of F, row S = y): Z = (f - mean) / ||f - mean||,
@@ -1787,6 +1784,54 @@ void fit_rows(discover_ctx* ctx, const discover_l0_problem* probs, int nb, int D
                                                        pb.ids, nullptr, rmse + b);
     }
     check_launch("k_omp_fit (rows)");
+}
+
+GramOut l0_gram_one(discover_ctx* ctx, const discover_l0_problem& pb, const std::string& name,
+                    hipStream_t st) {
+    PrepArgs a{};
+    a.n = pb.n; a.S = pb.S; a.ldz = (int)cdiv(pb.n, 16) * 16; a.ldg = (int)cdiv(pb.S + 1, 2) * 2;
+    a.F = pb.F; a.ldf = pb.ldf; a.y = pb.y;
+    a.Z = ctx->buf<double>(name + "_Z" + ctx->tag, (size_t)(pb.S + 1) * a.ldz);
+    a.G = ctx->buf<double>(name + "_G" + ctx->tag, (size_t)(pb.S + 1) * a.ldg);
+    a.yy = ctx->buf<double>(name + "_yy" + ctx->tag, 1);
+    a.dg = ctx->buf<double>(name + "_dg" + ctx->tag, (size_t)pb.S + 1);
+    const ctab<PrepArgs> dpa = ct((const PrepArgs*)ctx->upload(name + "_prep", &a, sizeof a, st));
+    KTimer kt(ctx, st, "l0_gram");
+    k_l0_prep<<<dim3((unsigned)cdiv(pb.S + 1, 4), 1), 256, 0, st>>>(dpa);
+    const int gt = (int)cdiv(pb.S + 1, 32);
+    k_gram<<<dim3(8u * (unsigned)gram_xcd_tiles(gt), 1, 1), 256, 0, st>>>(dpa);
+    check_launch("k_gram");
+    return GramOut{a.G, a.ldg, a.yy, a.dg};
+}
+
+// QR residual sum of squares of each listed D-subset (block-stride over the
+// list; the work space of a block is in LDS when it fits).
+__global__ __launch_bounds__(256) void k_refit_list(int n, int D, const double* __restrict__ F, int64_t ldf,
+                                                    const double* __restrict__ y,
+                                                    const int32_t* __restrict__ subs, int64_t count,
+                                                    double* __restrict__ rss_out, double* __restrict__ scratch,
+                                                    int64_t sld, int use_lds) {
+    __shared__ double coef[DISCOVER_MAX_D + 1];
+    __shared__ double rss;
+    extern __shared__ double dsm[];
+    double* A = use_lds ? dsm : scratch + (int64_t)blockIdx.x * sld;
+    for (int64_t e = blockIdx.x; e < count; e += gridDim.x) {
+        block_lsq(n, D, subs + e * D, F, ldf, y, A, coef, &rss, nullptr);
+        if (threadIdx.x == 0) rss_out[e] = rss;
+        __syncthreads();
+    }
+}
+
+void refit_list(discover_ctx* ctx, const discover_l0_problem& pb, int D, const int32_t* subs, int64_t count,
+                double* rss, hipStream_t st) {
+    if (count <= 0) return;
+    const int64_t sld = (int64_t)(D + 2) * pb.n;
+    const int use_lds = sld * 8 <= 65536 ? 1 : 0;
+    const unsigned grid = (unsigned)std::min<int64_t>(count, 2048);
+    double* scr = use_lds ? nullptr : ctx->buf<double>("refit_list_A" + ctx->tag, (size_t)grid * sld);
+    k_refit_list<<<grid, 256, use_lds ? sld * 8 : 0, st>>>(pb.n, D, pb.F, pb.ldf, pb.y, subs, count, rss, scr,
+                                                          sld, use_lds);
+    check_launch("k_refit_list");
 }
 
 void validate_omp(const discover_l0_problem* probs, int32_t n_problems, int32_t D_max,

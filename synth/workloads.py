@@ -229,6 +229,31 @@ def subspace3000():
             "planted_rows": sorted(int(r) for r in rows)}
 
 
+def subspace512():
+    """A subspace for the exact branch-and-bound L0: S = 512 rows over n =
+    2000 samples built like subspace3000's (products of two or three of 24
+    lognormal(0, 0.5) latent columns raised to powers in {-2, -1, 1, 2}); a
+    planted 5-row model with coefficients +-U[0.5, 2] on standardised rows,
+    intercept 0.5, 1 % noise; candidate IDs are 512 distinct values below
+    7e8.  D = 5 (C(512, 5) = 2.9e11 subsets)."""
+    rng = np.random.default_rng(7)
+    n, S, p, D = 2000, 512, 24, 5
+    Z = rng.lognormal(0.0, 0.5, size=(p, n))
+    F = np.empty((S, n))
+    for i in range(S):
+        k = int(rng.integers(2, 4))
+        cols = rng.choice(p, size=k, replace=False)
+        pw = rng.choice([-2, -1, 1, 2], size=k)
+        F[i] = np.prod([Z[c] ** e for c, e in zip(cols, pw)], axis=0)
+    rows = rng.choice(S, size=D, replace=False)
+    coef = rng.uniform(0.5, 2.0, size=D) * rng.choice([-1.0, 1.0], size=D)
+    yc = 0.5 + sum(c * (F[r] - F[r].mean()) / F[r].std() for c, r in zip(coef, rows))
+    y = yc + _noise(rng, yc, 0.01)
+    ids = np.sort(rng.choice(700_000_000, size=S, replace=False)).astype(np.int64)
+    return {"name": "subspace512", "F": F, "y": y, "ids": ids, "n": n, "S": S, "D": D,
+            "planted_rows": sorted(int(r) for r in rows)}
+
+
 def random_small(seed, p=4, n=30, rung=2, T=1, units_B=0, lo=0.5, hi=2.0):
     """Small random problem for brute-force cross checks."""
     rng = np.random.default_rng(seed)
