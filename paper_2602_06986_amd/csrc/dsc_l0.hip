@@ -1250,36 +1250,41 @@ __global__ __launch_bounds__(256) void k_omp_fit(int n, const double* __restrict
 }
 
 // ================================================================== host
-// D = 3 blocks (16 consecutive a, 64 consecutive c).  Column groups of 64
+// D = 3 blocks (16 consecutive a, 64 consecutive c, a range of b).  A block
+// reads the factor-table tile E[b range][a rows] (32 bytes per (a, b)) and
+// the G tile [b range][c columns] (8 bytes per (b, c)).  Groups of 16 a rows
 // are dealt to the 8 XCDs by longest-processing-time on their total work,
-// and block p of the grid runs on XCD p mod 8, so each XCD's L2 holds only
-// its own columns of G; within an XCD the heaviest blocks go first, and
-// blocks of equal work that share their a rows and b range run side by side
-// (they read the same factor-table entries).  Chunks of 96 rows give the C(1500, 3)
-// sweep 7112 blocks, about 28 per CU, enough to even out the tail.
-constexpr int SW3_BMAX = 96;          // b iterations per block
+// and block p of the grid runs on XCD p mod 8, so each XCD reads only its
+// own rows of E (72 MB at S = 1500, which every XCD read in full when the
+// XCDs were given column groups instead).  The b ranges are cut on a common
+// grid of 96 rows, so blocks of different a groups with the same (b range,
+// c columns) read the same G tile; each XCD runs its blocks in (b range, c
+// columns, a group) order, so that tile and the E tiles of its a groups for
+// that b range are in its L2 when the next blocks need them.  The C(1500, 3)
+// sweep has about 7600 blocks, some 30 per CU.
+constexpr int SW3_BMAX = 96;          // b iterations per block (and the grid of b ranges)
 
 static std::vector<int4> sweep3_blocks(int S) {
-    const int ngrp = (S + 63) / 64;
-    std::vector<std::vector<std::pair<int64_t, int4>>> per_grp(ngrp);
+    const int ngrp = (S + 15) / 16;
+    std::vector<std::vector<int4>> per_grp(ngrp);
     std::vector<int64_t> gwork(ngrp, 0);
     for (int cg = 0; cg < (S + 63) / 64; cg++) {
         const int c0 = 64 * cg, ch = std::min(S, c0 + 64);
         for (int a0 = 0; a0 < S - 2 && a0 + 2 < ch; a0 += 16) {
             const int bend = std::min(S - 1, c0 + 63);
-            const int g = cg;
-            for (int b0 = a0 + 1; b0 < bend; b0 += SW3_BMAX) {
-                const int b1 = std::min(bend, b0 + SW3_BMAX);
-                const int64_t work = (int64_t)(b1 - b0) * 16;
-                per_grp[g].push_back({work, make_int4(a0, c0, b0, b1)});
-                gwork[g] += work;
+            const int g = a0 / 16;
+            for (int b0 = a0 + 1; b0 < bend;) {
+                const int b1 = std::min(bend, (b0 / SW3_BMAX + 1) * SW3_BMAX);
+                per_grp[g].push_back(make_int4(a0, c0, b0, b1));
+                gwork[g] += (int64_t)(b1 - b0) * 16;
+                b0 = b1;
             }
         }
     }
     std::vector<int> order(ngrp);
     for (int g = 0; g < ngrp; g++) order[g] = g;
     std::sort(order.begin(), order.end(), [&](int x, int y) { return gwork[x] > gwork[y]; });
-    std::vector<std::vector<std::pair<int64_t, int4>>> q(8);
+    std::vector<std::vector<int4>> q(8);
     std::vector<int64_t> xwork(8, 0);
     for (int g : order) {
         const int x = (int)(std::min_element(xwork.begin(), xwork.end()) - xwork.begin());
@@ -1288,18 +1293,18 @@ static std::vector<int4> sweep3_blocks(int S) {
     }
     size_t mx = 0;
     for (auto& v : q) {
-        std::stable_sort(v.begin(), v.end(), [](const std::pair<int64_t, int4>& x,
-                                                const std::pair<int64_t, int4>& y) {
-            if (x.first != y.first) return x.first > y.first;
-            if (x.second.x != y.second.x) return x.second.x < y.second.x;
-            return x.second.z < y.second.z;
+        std::stable_sort(v.begin(), v.end(), [](const int4& x, const int4& y) {
+            const int bx = x.z / SW3_BMAX, by = y.z / SW3_BMAX;
+            if (bx != by) return bx < by;
+            if (x.y != y.y) return x.y < y.y;
+            return x.x < y.x;
         });
         mx = std::max(mx, v.size());
     }
     std::vector<int4> out;
     out.reserve(mx * 8);
     for (size_t i = 0; i < mx; i++)
-        for (int x = 0; x < 8; x++) out.push_back(i < q[x].size() ? q[x][i].second : make_int4(-1, 0, 0, 0));
+        for (int x = 0; x < 8; x++) out.push_back(i < q[x].size() ? q[x][i] : make_int4(-1, 0, 0, 0));
     return out;
 }
 
