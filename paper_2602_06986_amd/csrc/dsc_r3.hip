@@ -474,15 +474,15 @@ typedef __attribute__((ext_vector_type(8))) __bf16 r3_bf16x8;
 typedef __attribute__((ext_vector_type(4))) float r3_f32x4;
 typedef __attribute__((ext_vector_type(4))) unsigned r3_u32x4;
 
-// Two FP32 values rounded to BF16 (nearest, ties to even) and packed, with
-// plain integer operations: lo in bits 0..15, hi in bits 16..31 (finite
-// inputs; the rounding is explicit and identical in the layout kernel and
-// the screen).
+// Two FP32 values rounded to BF16 (nearest, ties to even: gfx950's packed
+// conversion) and packed, lo in bits 0..15, hi in bits 16..31; the layout
+// kernel and the screen round the same way.
 __device__ __forceinline__ unsigned r3_bf16_pack(float lo, float hi) {
-    unsigned a = __float_as_uint(lo), b = __float_as_uint(hi);
-    a += 0x7FFFu + ((a >> 16) & 1u);
-    b += 0x7FFFu + ((b >> 16) & 1u);
-    return (a >> 16) | (b & 0xFFFF0000u);
+    typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+    bf2 v;
+    v[0] = (__bf16)lo;
+    v[1] = (__bf16)hi;
+    return __builtin_bit_cast(unsigned, v);
 }
 
 // Right-hand operands of the precision form: b64[((c 2 + v) NC + ch) 512 +
@@ -521,6 +521,7 @@ struct R3lpArgs {
     R3mArgs m;
     const double* b64;
     const __bf16* blp;
+    const double* r2q;        // mean square of each rung-2 feature (by id - off[2])
     int NC;
     double delta;
 };
@@ -554,13 +555,12 @@ __global__ __launch_bounds__(256) void k_r3_lp(R3lpArgs a) {
     }
     r3_v4d s1[GT], s2[GT];
     r3_f32x4 pa[GT][TP];
-    double gmx[GT], gmn[GT];
+    double hmx[GT];                                      // div tiles: max |1/g| of the lane's samples
 #pragma unroll
     for (int u = 0; u < GT; u++) {
         s1[u] = r3_v4d{0.0, 0.0, 0.0, 0.0};
         s2[u] = r3_v4d{0.0, 0.0, 0.0, 0.0};
-        gmx[u] = 0.0;
-        gmn[u] = INFINITY;
+        hmx[u] = 0.0;
 #pragma unroll
         for (int t = 0; t < TP; t++) pa[u][t] = r3_f32x4{0.f, 0.f, 0.f, 0.f};
     }
@@ -589,8 +589,13 @@ __global__ __launch_bounds__(256) void k_r3_lp(R3lpArgs a) {
     };
     Ld cur, nxt;
     load(0, cur);
+    // Only the last chunk holds samples >= n: there the row values are set
+    // to 0 (the right-hand operands are 0 too, but a row value there may be
+    // inf or NaN).  A row whose feature is invalid only reaches its own row
+    // of the products, whose scores are never stored, so it is not masked.
     for (int ch = 0; ch < a.NC; ch++) {
         const int s = 32 * ch + 8 * kq;
+        const bool tail = ch == a.NC - 1;
         load(ch + 1 < a.NC ? ch + 1 : ch, nxt);
         const r3_v4d b1a = cur.b1[0], b1b = cur.b1[1];
         const r3_v4d b2a = b1a * b1a, b2b = b1b * b1b;
@@ -606,13 +611,10 @@ __global__ __launch_bounds__(256) void k_r3_lp(R3lpArgs a) {
             float vf[8];
 #pragma unroll
             for (int e = 0; e < 8; e++) {
-                const bool in = rok[u] && s + e < g.n;
-                double x = in ? v[e] : 0.0;
-                if (in) {
-                    gmx[u] = fmax(gmx[u], fabs(x));
-                    gmn[u] = fmin(gmn[u], fabs(x));
-                }
-                if (hk) x = in ? r3_rcp(x) : 0.0;
+                double x = v[e];
+                if (hk) x = r3_rcp(x);
+                if (tail && s + e >= g.n) x = 0.0;
+                if (hk) hmx[u] = fmax(hmx[u], fabs(x));
                 v[e] = x;
                 vf[e] = (float)x;
             }
@@ -645,10 +647,10 @@ __global__ __launch_bounds__(256) void k_r3_lp(R3lpArgs a) {
     unsigned cnt = 0;
 #pragma unroll
     for (int u = 0; u < GT; u++) {
-        gmx[u] = fmax(gmx[u], __shfl_xor(gmx[u], 16, 64));
-        gmx[u] = fmax(gmx[u], __shfl_xor(gmx[u], 32, 64));
-        gmn[u] = fmin(gmn[u], __shfl_xor(gmn[u], 16, 64));
-        gmn[u] = fmin(gmn[u], __shfl_xor(gmn[u], 32, 64));
+        if (hk) {
+            hmx[u] = fmax(hmx[u], __shfl_xor(hmx[u], 16, 64));
+            hmx[u] = fmax(hmx[u], __shfl_xor(hmx[u], 32, 64));
+        }
         // FP64 results: row kq + 4r in register r; wanted: row 4 kq + e in slot e
         double S1[4], S2[4];
 #pragma unroll
@@ -666,8 +668,14 @@ __global__ __launch_bounds__(256) void k_r3_lp(R3lpArgs a) {
             const int i = 4 * kq + e;                      // row of slot e
             const bool ok = __shfl((int)rok[u], i, 64) != 0 && colok;
             const int64_t gj = __shfl(j2[u], i, 64);
-            const double rmx = __shfl(gmx[u], i, 64), rmn = __shfl(gmn[u], i, 64);
+            const double hx = hk ? __shfl(hmx[u], i, 64) : 0.0;
             if (!ok) continue;
+            // max |g| <= sqrt(sum g^2) = sqrt(n E[g^2]) (E[g^2] recorded by the
+            // rung-2 screen; 1 % margin for its rounding): only compared with
+            // range limits many orders of magnitude away; min |g| = 1 / max
+            // |1/g| (div tiles only)
+            const double rmx = sqrt(nn * a.r2q[gj - g.sd.off[2]]) * 1.01;
+            const double rmn = hk ? 1.0 / hx : 0.0;
             const int64_t id = pair_id(g.sd, 3, op3, praw, gj);
             bool sure;
             double amx, fmx, bmx;                          // largest |A|, |f|, |B| of the products
@@ -886,7 +894,7 @@ void launch_r3(discover_ctx* ctx, const R3Launch& a, hipStream_t st) {
         m.valid = a.valid; m.mat_raw = a.mat_raw; m.r2v = a.r2v; m.ysum = a.ysum; m.sd = a.sd;
         m.N = a.N; m.scores = a.scores; m.nscored = a.nscored; m.fix_ids = a.fix_ids;
         m.fix_cnt = a.fix_cnt; m.fix_cap = a.fix_cap;
-        l.b64 = b64; l.blp = blp; l.NC = NC; l.delta = a.delta;
+        l.b64 = b64; l.blp = blp; l.r2q = a.r2q; l.NC = NC; l.delta = a.delta;
         KTimer kt(ctx, st, "screen_r3");
         switch (a.TP) {
         case 1: launch_lp<1, 1>(l, P.n_ctiles, P.n_grec, st); break;
