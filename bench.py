@@ -51,11 +51,11 @@ SWEEP3_COUNTERS = {
 # device copy.  Valid only for the kernel source they were taken on.
 R3_COUNTERS = {
     "k_r3_lp": {"source": "paper_2602_06986_amd/csrc/dsc_r3.hip",
-                "sha256": "b6eed7e448dca81c6028128d34cc7ca2c5cc8eae8960fc0fcf77bd8e633a7974",
-                "fetch_kib": 27410337.9, "fetch_scale": 1.99992, "write_kib": 1312742.1, "write_scale": 1.0},
+                "sha256": "4048ecd8c0ceb2027177e2553b791c21d653ac704a1d0d37919aa30fbfa0a04d",
+                "fetch_kib": 36648076.8, "fetch_scale": 1.99992, "write_kib": 1315454.6, "write_scale": 1.0},
     "k_r3_mm": {"source": "paper_2602_06986_amd/csrc/dsc_r3.hip",
-                "sha256": "b6eed7e448dca81c6028128d34cc7ca2c5cc8eae8960fc0fcf77bd8e633a7974",
-                "fetch_kib": 23713848.6, "fetch_scale": 1.99992, "write_kib": 1300197.9, "write_scale": 1.0},
+                "sha256": "4048ecd8c0ceb2027177e2553b791c21d653ac704a1d0d37919aa30fbfa0a04d",
+                "fetch_kib": 26298420.9, "fetch_scale": 1.99992, "write_kib": 1302629.0, "write_scale": 1.0},
 }
 
 
