@@ -46,28 +46,9 @@ extern "C" int64_t discover_count(int32_t p, const discover_screen_params* prm) 
     discover_status s = guarded([&] {
         DSC_REQUIRE(prm && p >= 1, "prm/p");
         DSC_REQUIRE(prm->rung >= 0 && prm->rung <= DISCOVER_MAX_RUNG, "rung");
-        SpaceDev d{};
-        Space sp;
-        discover_screen_params q = *prm;
-        // counting needs no operand plan: build the layout only
-        d.p = p;
-        d.R = q.rung;
-        d.L[0] = p;
-        d.off[1] = p;
-        for (int r = 1; r <= d.R; r++) {
-            const uint32_t m = (q.rung_ops[r] ? q.rung_ops[r] : q.ops) & DISCOVER_OPS_ALL;
-            const int pool = q.rung_pool[r] < 0 ? r - 1 : q.rung_pool[r];
-            DSC_REQUIRE(pool <= r - 1, "rung_pool");
-            const int64_t np = pool == r - 1 ? choose2(d.off[r]) - choose2(d.off[r - 1])
-                                             : d.L[r - 1] * d.off[pool + 1];
-            int64_t L = 0;
-            for (int o = 0; o < 10; o++)
-                if (m >> o & 1u) L += o < OP_ADD ? d.L[r - 1] : np;
-            d.L[r] = L;
-            d.off[r + 1] = d.off[r] + L;
-        }
+        SpaceDev d;
+        space_layout(d, p, *prm);                // counting needs no operand plan
         out = d.off[d.R + 1];
-        (void)sp;
     });
     return s == DISCOVER_OK ? out : (int64_t)s;
 }
@@ -79,27 +60,8 @@ extern "C" discover_status discover_decode(int32_t p, const discover_screen_para
         DSC_REQUIRE(prm && buf && len > 0, "prm/buf/len");
         const int64_t N = discover_count(p, prm);
         DSC_REQUIRE(N > 0 && id >= 0 && id < N, "id %lld outside the space", (long long)id);
-        // layout only (operand plan not needed): mirror build_space's block table
-        SpaceDev d{};
-        d.p = p;
-        d.R = prm->rung;
-        d.L[0] = p;
-        d.off[1] = p;
-        for (int o = 0; o < 10; o++) d.block[0][o] = -1;
-        for (int r = 1; r <= d.R; r++) {
-            d.ops[r] = (prm->rung_ops[r] ? prm->rung_ops[r] : prm->ops) & DISCOVER_OPS_ALL;
-            d.pool[r] = prm->rung_pool[r] < 0 ? r - 1 : prm->rung_pool[r];
-            d.npairs[r] = d.pool[r] == r - 1 ? choose2(d.off[r]) - choose2(d.off[r - 1])
-                                              : d.L[r - 1] * d.off[d.pool[r] + 1];
-            int64_t at = d.off[r];
-            for (int o = 0; o < 10; o++) {
-                if (!(d.ops[r] >> o & 1u)) { d.block[r][o] = -1; continue; }
-                d.block[r][o] = at;
-                at += o < OP_ADD ? d.L[r - 1] : d.npairs[r];
-            }
-            d.L[r] = at - d.off[r];
-            d.off[r + 1] = at;
-        }
+        SpaceDev d;
+        space_layout(d, p, *prm);
         const std::string s = expr_of(d, id);
         std::snprintf(buf, len, "%s", s.c_str());
     });

@@ -57,13 +57,8 @@ bool unit_rule(int op, int B, const int32_t* ua, const int32_t* ub, int32_t* out
     return false;
 }
 
-static int popcount(uint32_t v) { return __builtin_popcount(v); }
-
-void build_space(Space& sp, int p, const discover_screen_params& prm, int B,
-                 const int32_t* units) {
-    SpaceDev& d = sp.d;
+void space_layout(SpaceDev& d, int p, const discover_screen_params& prm) {
     std::memset(&d, 0, sizeof d);
-    sp.B = B;
     d.p = p;
     d.R = prm.rung;
     d.L[0] = p;
@@ -89,10 +84,16 @@ void build_space(Space& sp, int p, const discover_screen_params& prm, int B,
         }
         d.L[r] = id - d.off[r];
         d.off[r + 1] = id;
-        (void)popcount;
     }
     for (int r = d.R + 1; r < 4; r++)
         for (int o = 0; o < 10; o++) d.block[r][o] = -1;
+}
+
+void build_space(Space& sp, int p, const discover_screen_params& prm, int B,
+                 const int32_t* units) {
+    SpaceDev& d = sp.d;
+    space_layout(d, p, prm);
+    sp.B = B;
 
     // Rung 3 is supported as an operator-limited rung: binary operators whose
     // first operand comes from a materialised rung (partner pool <= 1); the

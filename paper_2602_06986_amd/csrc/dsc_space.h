@@ -98,6 +98,10 @@ struct Space {
 };
 
 // Build the space; `units` is host [p][B] (may be NULL when B = 0).
+// The canonical layout of the raw space (rung sizes, offsets, operator
+// blocks): the ID enumeration that build_space, discover_count and
+// discover_decode share.
+void space_layout(SpaceDev& d, int p, const discover_screen_params& prm);
 void build_space(Space& sp, int p, const discover_screen_params& prm, int B,
                  const int32_t* units);
 
