@@ -485,31 +485,43 @@ __device__ __forceinline__ unsigned r3_bf16_pack(float lo, float hi) {
     return __builtin_bit_cast(unsigned, v);
 }
 
-// Right-hand operands of the precision form: b64[((c 2 + v) NC + ch) 512 +
-// 8 l + e] = x (v = 0) or x^2 (v = 1) of column l%16 at sample 32 ch +
-// 8 (l/16) + e; blp[((c TP + t) NC + ch) 512 + 8 l + e] = BF16(x y_t) there.
+// Right-hand operands of the precision form, per column tile c and 32-sample
+// chunk ch (512 entries each): b64[(c NC + ch) 512 + 128 q + 2 L + i] = x of
+// column L%16 at sample 32 ch + 8 (L/16) + 2 q + i (pairs of samples, lane
+// L's pair q contiguous across lanes, so that a 16-byte read per lane covers
+// one pair of every lane); blp[((c TP + t) NC + ch) 512 + 8 l + e] =
+// BF16(x y_t) of column l%16 at sample 32 ch + 8 (l/16) + e.
 __global__ __launch_bounds__(256) void k_r3_bmat_lp(int n, int64_t ldn, int TP, int NC, int nct,
                                                     const int32_t* __restrict__ coldesc,
                                                     const double* __restrict__ Vf, const double* __restrict__ Rf,
                                                     const double* __restrict__ Yn, double* __restrict__ b64,
                                                     __bf16* __restrict__ blp) {
     const int64_t per = (int64_t)NC * 512;
-    const int64_t total = (int64_t)nct * (2 + TP) * per;
+    const int64_t total = (int64_t)nct * (1 + TP) * per;
     for (int64_t f = (int64_t)blockIdx.x * 256 + threadIdx.x; f < total; f += (int64_t)gridDim.x * 256) {
         const int64_t r = f % per, ck = f / per;
-        const int c = (int)(ck / (2 + TP)), v = (int)(ck % (2 + TP));
-        const int ch = (int)(r / 512), l = (int)((r % 512) / 8), e = (int)(r % 8);
-        const int j = l & 15, s = 32 * ch + 8 * (l >> 4) + e;
+        const int c = (int)(ck / (1 + TP)), v = (int)(ck % (1 + TP));
+        const int ch = (int)(r / 512), w = (int)(r % 512);
+        int j, s;
+        if (v == 0) {
+            const int q = w >> 7, L = (w & 127) >> 1, i = w & 1;
+            j = L & 15;
+            s = 32 * ch + 8 * (L >> 4) + 2 * q + i;
+        } else {
+            const int l = w >> 3, e = w & 7;
+            j = l & 15;
+            s = 32 * ch + 8 * (l >> 4) + e;
+        }
         const int32_t d = coldesc[c * 16 + j];
         double x = 0.0;
         if (d >= 0 && s < n) {
             const int p = d & 0xFFFF, kind = d >> 16;
             x = kind == 3 ? 1.0 : kind == 1 ? Rf[(int64_t)p * ldn + s] : Vf[(int64_t)p * ldn + s];
         }
-        if (v < 2) {
-            b64[((int64_t)c * 2 + v) * per + r] = v == 0 ? x : x * x;
+        if (v == 0) {
+            b64[(int64_t)c * per + r] = x;
         } else {
-            const int t = v - 2;
+            const int t = v - 1;
             const double yv = (s < n) ? Yn[(int64_t)t * ldn + s] : 0.0;
             const unsigned pk = r3_bf16_pack((float)(x * yv), 0.0f);
             blp[((int64_t)c * TP + t) * per + r] = __builtin_bit_cast(__bf16, (unsigned short)(pk & 0xFFFFu));
@@ -523,18 +535,34 @@ struct R3lpArgs {
     const __bf16* blp;
     const double* r2q;        // mean square of each rung-2 feature (by id - off[2])
     int NC;
+    int ct0;                  // first column tile of the launch
     double delta;
 };
 
-template <int TP, int GT>
-__global__ __launch_bounds__(256) void k_r3_lp(R3lpArgs a) {
+typedef double r3_v2d __attribute__((ext_vector_type(2)));
+
+// A block's four waves take four row tiles against one column tile; the
+// column tile's operands of a chunk (x, x^2 and the TP products x y_t: 8 +
+// TP KB) are staged once per block in LDS, double-buffered, and each wave
+// reads them there (16 contiguous bytes per lane per read).  The next
+// chunk's operands are loaded into registers (a share of 16 (1 + TP/4) bytes
+// per thread) and the next chunk's row operands per wave while the current
+// chunk's products are issued.
+// HK: the launch's column tiles multiply 1/g (div), else g (mul, rdiv);
+// the two kinds are separate launches, so that neither carries the
+// other's per-sample work.
+template <int TP, int GT, bool HK>
+__global__ __launch_bounds__(256, (TP <= 8 ? 2 : 1)) void k_r3_lp(R3lpArgs a) {
     const R3mArgs& g = a.m;
-    const int lane = threadIdx.x & 63;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
     const int r16 = lane & 15, kq = lane >> 4;
-    const int ct = blockIdx.x / g.n_gblk;
-    const int64_t tile0 = ((int64_t)(blockIdx.x - ct * g.n_gblk) * 4 + r3_wave()) * GT;
-    if (tile0 * 16 >= g.n_grec) return;
-    const bool hk = ct >= g.n_gct;
+    const int cb = blockIdx.x / g.n_gblk;
+    const int ct = a.ct0 + cb;
+    const int64_t tile0 = ((int64_t)(blockIdx.x - cb * g.n_gblk) * 4 + r3_wave()) * GT;
+    // a wave without a row tile still stages its share and meets every barrier
+    const bool active = tile0 * 16 < g.n_grec;
+    constexpr bool hk = HK;
     bool rok[GT];
     int64_t j2[GT];
     int oo[GT];
@@ -564,16 +592,43 @@ __global__ __launch_bounds__(256) void k_r3_lp(R3lpArgs a) {
 #pragma unroll
         for (int t = 0; t < TP; t++) pa[u][t] = r3_f32x4{0.f, 0.f, 0.f, 0.f};
     }
-    const double* b1p = a.b64 + ((int64_t)ct * 2 * a.NC) * 512 + lane * 8;
-    const __bf16* bl = a.blp + ((int64_t)ct * TP * a.NC) * 512 + lane * 8;
-    // operands of chunk ch: the row operands (8 samples of two operand rows
-    // per tile) and the right-hand x and x y_t; the next chunk's are loaded
-    // before this chunk's products are issued
-    struct Ld {
-        r3_v4d x1[GT][2], x2[GT][2], b1[2];
-        r3_bf16x8 bv[TP];
+    // LDS buffer: x (512 doubles, pair-major as in b64), x^2 (same), then
+    // the TP x y_t blocks (512 BF16 each, lane-major as in blp)
+    constexpr int BUF = (8 + TP) * 1024;
+    __shared__ __attribute__((aligned(16))) char smem[2 * BUF];
+    constexpr int NPB = (TP * 64 + 255) / 256;           // 16-byte pieces of x y_t per thread
+    const double* gx = a.b64 + (int64_t)ct * a.NC * 512;
+    const __bf16* gb = a.blp + (int64_t)ct * TP * a.NC * 512;
+    r3_v2d sx;
+    r3_u32x4 sb[NPB];
+    // piece i of thread tid: q = tid + 256 i (with fewer than 256 pieces,
+    // threads share pieces and write the same bytes); every thread loads and
+    // stores on every chunk, so that no load sits behind a branch
+    auto piece = [&](int i) { return TP * 64 >= 256 ? tid + 256 * i : (tid & (TP * 64 - 1)); };
+    auto stage_load = [&](int ch) {
+        sx = *(const r3_v2d*)(gx + (int64_t)ch * 512 + 2 * tid);
+#pragma unroll
+        for (int i = 0; i < NPB; i++) {
+            const int q = piece(i);
+            sb[i] = *(const r3_u32x4*)(gb + ((int64_t)(q >> 6) * a.NC + ch) * 512 + (q & 63) * 8);
+        }
     };
-    auto load = [&](int ch, Ld& L) {
+    auto stage_store = [&](int buf) {
+        double* xs = (double*)(smem + buf * BUF);
+        *(r3_v2d*)(xs + 2 * tid) = sx;
+        *(r3_v2d*)(xs + 512 + 2 * tid) = sx * sx;
+        char* bs = smem + buf * BUF + 8192;
+#pragma unroll
+        for (int i = 0; i < NPB; i++) {
+            const int q = piece(i);
+            *(r3_u32x4*)(bs + (q >> 6) * 1024 + (q & 63) * 16) = sb[i];
+        }
+    };
+    // row operands of chunk ch: 8 samples of two operand rows per tile
+    struct Ld {
+        r3_v4d x1[GT][2], x2[GT][2];
+    };
+    auto load_rows = [&](int ch, Ld& L) {
         const int s = 32 * ch + 8 * kq;
 #pragma unroll
         for (int u = 0; u < GT; u++)
@@ -582,61 +637,76 @@ __global__ __launch_bounds__(256) void k_r3_lp(R3lpArgs a) {
                 L.x1[u][h] = *(const r3_v4d*)(p1[u] + s + 4 * h);
                 L.x2[u][h] = *(const r3_v4d*)(p2[u] + s + 4 * h);
             }
-        L.b1[0] = *(const r3_v4d*)(b1p + (int64_t)ch * 512);
-        L.b1[1] = *(const r3_v4d*)(b1p + (int64_t)ch * 512 + 4);
-#pragma unroll
-        for (int t = 0; t < TP; t++) L.bv[t] = *(const r3_bf16x8*)(bl + ((int64_t)t * a.NC + ch) * 512);
     };
     Ld cur, nxt;
-    load(0, cur);
+    stage_load(0);
+    load_rows(0, cur);
+    stage_store(0);
+    __syncthreads();
     // Only the last chunk holds samples >= n: there the row values are set
     // to 0 (the right-hand operands are 0 too, but a row value there may be
     // inf or NaN).  A row whose feature is invalid only reaches its own row
     // of the products, whose scores are never stored, so it is not masked.
+    // (the last chunk reloads itself into the idle buffer: unused)
     for (int ch = 0; ch < a.NC; ch++) {
-        const int s = 32 * ch + 8 * kq;
-        const bool tail = ch == a.NC - 1;
-        load(ch + 1 < a.NC ? ch + 1 : ch, nxt);
-        const r3_v4d b1a = cur.b1[0], b1b = cur.b1[1];
-        const r3_v4d b2a = b1a * b1a, b2b = b1b * b1b;
-#pragma unroll
-        for (int u = 0; u < GT; u++) {
-            double v[8];
-#pragma unroll
-            for (int h = 0; h < 2; h++) {
-                const r3_v4d w = r3_combine(oo[u], cur.x1[u][h], cur.x2[u][h]);
-#pragma unroll
-                for (int e = 0; e < 4; e++) v[4 * h + e] = w[e];
-            }
-            float vf[8];
-#pragma unroll
-            for (int e = 0; e < 8; e++) {
-                double x = v[e];
-                if (hk) x = r3_rcp(x);
-                if (tail && s + e >= g.n) x = 0.0;
-                if (hk) hmx[u] = fmax(hmx[u], fabs(x));
-                v[e] = x;
-                vf[e] = (float)x;
-            }
+        const int cn = ch + 1 < a.NC ? ch + 1 : ch;
+        stage_load(cn);
+        load_rows(cn, nxt);
+        if (active) {
+            const int s = 32 * ch + 8 * kq;
+            const bool tail = ch == a.NC - 1;
+            const double* xs = (const double*)(smem + (ch & 1) * BUF);
+            const char* bs = smem + (ch & 1) * BUF + 8192;
+            r3_v2d xp[4], x2p[4];
 #pragma unroll
             for (int q = 0; q < 4; q++) {
-                s1[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[q], b1a[q], s1[u], 0, 0, 0);
-                s2[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[q] * v[q], b2a[q], s2[u], 0, 0, 0);
+                xp[q] = *(const r3_v2d*)(xs + 128 * q + 2 * lane);
+                x2p[q] = *(const r3_v2d*)(xs + 512 + 128 * q + 2 * lane);
             }
 #pragma unroll
-            for (int q = 0; q < 4; q++) {
-                s1[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[4 + q], b1b[q], s1[u], 0, 0, 0);
-                s2[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[4 + q] * v[4 + q], b2b[q], s2[u], 0, 0, 0);
-            }
-            const r3_u32x4 au = {r3_bf16_pack(vf[0], vf[1]), r3_bf16_pack(vf[2], vf[3]),
-                                 r3_bf16_pack(vf[4], vf[5]), r3_bf16_pack(vf[6], vf[7])};
-            const r3_bf16x8 av = __builtin_bit_cast(r3_bf16x8, au);
+            for (int u = 0; u < GT; u++) {
+                double v[8];
 #pragma unroll
-            for (int t = 0; t < TP; t++)
-                pa[u][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, cur.bv[t], pa[u][t], 0, 0, 0);
+                for (int h = 0; h < 2; h++) {
+                    const r3_v4d w = r3_combine(oo[u], cur.x1[u][h], cur.x2[u][h]);
+#pragma unroll
+                    for (int e = 0; e < 4; e++) v[4 * h + e] = w[e];
+                }
+                float vf[8];
+#pragma unroll
+                for (int e = 0; e < 8; e++) {
+                    double x = v[e];
+                    if (hk) x = r3_rcp(x);
+                    if (tail && s + e >= g.n) x = 0.0;
+                    if (hk) hmx[u] = fabs(x) > hmx[u] ? fabs(x) : hmx[u];   // NaN leaves it unchanged
+                    v[e] = x;
+                    // FP64 -> FP32 here and FP32 -> BF16 in the pack: two
+                    // hardware roundings (the error bound counts both); the
+                    // empty asm keeps the compiler from fusing them into one
+                    // correctly rounded (and much longer) conversion
+                    vf[e] = (float)x;
+                    __asm__("" : "+v"(vf[e]));
+                }
+#pragma unroll
+                for (int e = 0; e < 8; e++) {
+                    s1[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[e], xp[e >> 1][e & 1], s1[u], 0, 0, 0);
+                    s2[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[e] * v[e], x2p[e >> 1][e & 1], s2[u], 0, 0, 0);
+                }
+                const r3_u32x4 au = {r3_bf16_pack(vf[0], vf[1]), r3_bf16_pack(vf[2], vf[3]),
+                                     r3_bf16_pack(vf[4], vf[5]), r3_bf16_pack(vf[6], vf[7])};
+                const r3_bf16x8 av = __builtin_bit_cast(r3_bf16x8, au);
+#pragma unroll
+                for (int t = 0; t < TP; t++) {
+                    const r3_bf16x8 bv = *(const r3_bf16x8*)(bs + t * 1024 + lane * 16);
+                    pa[u][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, pa[u][t], 0, 0, 0);
+                }
+            }
         }
+        stage_store((ch + 1) & 1);
+        __syncthreads();
         cur = nxt;
     }
+    if (!active) return;
     const int32_t cd = g.coldesc[ct * 16 + r16];
     const int p = cd & 0xFFFF, kind = cd >> 16;
     const int op3 = kind == 0 ? OP_MUL : kind == 1 ? OP_RDIV : OP_DIV;
@@ -723,12 +793,20 @@ __global__ __launch_bounds__(256) void k_r3_lp(R3lpArgs a) {
     if (lane == 0 && cnt) atomicAdd(g.nscored, (unsigned long long)cnt);
 }
 
+// One launch over the mul / rdiv column tiles [0, n_gct), one over the div
+// tiles [n_gct, nct).
 template <int TP, int GT>
-void launch_lp(R3lpArgs l, int nct, int64_t n_grec, hipStream_t st) {
+void launch_lp(R3lpArgs l, int n_gct, int nct, int64_t n_grec, hipStream_t st) {
     l.m.n_gblk = (int)((n_grec / 16 + 4 * GT - 1) / (4 * GT));
-    const int64_t blocks = (int64_t)l.m.n_gblk * nct;
-    DSC_REQUIRE(blocks < ((int64_t)1 << 31), "rung-3 grid too large");
-    k_r3_lp<TP, GT><<<(unsigned)blocks, 256, 0, st>>>(l);
+    DSC_REQUIRE((int64_t)l.m.n_gblk * nct < ((int64_t)1 << 31), "rung-3 grid too large");
+    if (n_gct > 0) {
+        l.ct0 = 0;
+        k_r3_lp<TP, GT, false><<<(unsigned)((int64_t)l.m.n_gblk * n_gct), 256, 0, st>>>(l);
+    }
+    if (nct > n_gct) {
+        l.ct0 = n_gct;
+        k_r3_lp<TP, GT, true><<<(unsigned)((int64_t)l.m.n_gblk * (nct - n_gct)), 256, 0, st>>>(l);
+    }
 }
 
 template <class T>
@@ -881,8 +959,8 @@ void launch_r3(discover_ctx* ctx, const R3Launch& a, hipStream_t st) {
         check_launch("k_r3_pstat");
         const int NC = r3_chunks(a.n);
         double* b64 = a.bmat;
-        __bf16* blp = (__bf16*)(a.bmat + (size_t)P.n_ctiles * 2 * NC * 512);
-        const int64_t tot = (int64_t)P.n_ctiles * (a.TP + 2) * NC * 512;
+        __bf16* blp = (__bf16*)(a.bmat + (size_t)P.n_ctiles * NC * 512);
+        const int64_t tot = (int64_t)P.n_ctiles * (a.TP + 1) * NC * 512;
         k_r3_bmat_lp<<<(unsigned)std::min<int64_t>(cdiv(tot, 256), 16384), 256, 0, st>>>(
             a.n, a.ldn, a.TP, NC, P.n_ctiles, P.coldesc, a.Vf, a.Rf, a.Yn, b64, blp);
         check_launch("k_r3_bmat_lp");
@@ -897,11 +975,11 @@ void launch_r3(discover_ctx* ctx, const R3Launch& a, hipStream_t st) {
         l.b64 = b64; l.blp = blp; l.r2q = a.r2q; l.NC = NC; l.delta = a.delta;
         KTimer kt(ctx, st, "screen_r3");
         switch (a.TP) {
-        case 1: launch_lp<1, 1>(l, P.n_ctiles, P.n_grec, st); break;
-        case 2: launch_lp<2, 1>(l, P.n_ctiles, P.n_grec, st); break;
-        case 4: launch_lp<4, 1>(l, P.n_ctiles, P.n_grec, st); break;
-        case 8: launch_lp<8, 1>(l, P.n_ctiles, P.n_grec, st); break;
-        default: launch_lp<16, 1>(l, P.n_ctiles, P.n_grec, st); break;
+        case 1: launch_lp<1, 1>(l, P.n_gct, P.n_ctiles, P.n_grec, st); break;
+        case 2: launch_lp<2, 1>(l, P.n_gct, P.n_ctiles, P.n_grec, st); break;
+        case 4: launch_lp<4, 1>(l, P.n_gct, P.n_ctiles, P.n_grec, st); break;
+        case 8: launch_lp<8, 1>(l, P.n_gct, P.n_ctiles, P.n_grec, st); break;
+        default: launch_lp<16, 1>(l, P.n_gct, P.n_ctiles, P.n_grec, st); break;
         }
         check_launch("k_r3_lp");
     } else if (P.n_grec && P.n_ctiles) {
