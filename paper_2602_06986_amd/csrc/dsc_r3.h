@@ -50,11 +50,14 @@ std::shared_ptr<R3Plan> build_r3_plan(const Space& sp, uint32_t r3_ops);
 // Per-call buffers of one problem's rung-3 screen.
 inline int r3_quads(int n) { return 4 * (int)((n + 15) / 16); }
 inline int r3_chunks(int n) { return (int)((n + 31) / 32); }
+// Error coefficient of the precision form's FP32 moments: the score of a
+// rung-3 candidate moves by at most cm kappa through them (3 (n + 8) 2^-24).
+inline double r3_moment_err(int n) { return 3.0 * (n + 8) * 5.9604644775390625e-8; }
 // The main tiles' operands (FP64 layout, or the precision form's), then the
 // add/sub tiles' (FP64 layout) at r3_as_offset bytes.
 inline size_t r3_as_offset(const R3Plan& p, int TP, int n) {
     const size_t f64 = (size_t)p.n_ctiles * (TP + 2) * r3_quads(n) * 64 * 8;
-    const size_t lp = (size_t)p.n_ctiles * r3_chunks(n) * 512 * (2 * 8 + TP * 2);
+    const size_t lp = (size_t)p.n_ctiles * r3_chunks(n) * 512 * (4 + TP * 2);
     return (std::max(f64, lp) + 255) & ~(size_t)255;
 }
 inline size_t r3_bmat_bytes(const R3Plan& p, int TP, int n) {

@@ -447,27 +447,35 @@ __global__ __launch_bounds__(256) void k_r3_mm(R3mArgs g) {
 }
 
 // ------------------------------------------------------------ precision form
-// BF16 numerators, FP64 moments.  Per 32-sample chunk a lane regenerates 8
-// consecutive samples of its row (rows 16 rung-2 features, as above).  S1
-// and S2 come from 8 + 8 FP64 MFMAs against [x | x^2] (sample 8(l/16) + q of
-// the chunk in MFMA q); the T numerators from one v_mfma_f32_16x16x32_bf16
+// BF16 numerators, FP32 moments.  Per 32-sample chunk a lane regenerates 8
+// consecutive samples of its row (rows 16 rung-2 features, as above) in
+// FP64 and rounds them to FP32.  S1 and S2 come from 8 + 8
+// v_mfma_f32_16x16x4f32 against [x | x^2] in FP32 (sample 8(l/16) + e of
+// the chunk in MFMA e); the T numerators from one v_mfma_f32_16x16x32_bf16
 // each against x y_t rounded to BF16 (lane l supplies row l%16 at samples
-// 8(l/16)..+7 and column l%16 at the same samples, and receives
-// D[4(l/16)+e][l%16]).  The FP64 results are moved to the FP32 layout by
-// register shuffles before the epilogue.
+// 8(l/16)..+7 and column l%16 at the same samples).  Every product lands in
+// the same layout: lane l holds D[4(l/16)+e][l%16] in slot e.
 //
 // Error: with u = 2^-8 (plus the FP64 -> FP32 -> BF16 double rounding) the
 // product of two rounded values is within 2u + u^2 of the true product and
 // the FP32 sum adds gamma_n, so |P_lp - P| <= delta ||f|| ||y_t|| and
 // |r_lp - r| <= delta sqrt(kappa) with kappa = S2 / (S2 - S1^2/n): delta is
-// the precision form's BF16 bound.  Scores with kappa <= LP_KAPPA are stored
-// (error within the selection margin); others store the upper bound
-// -(s + delta sqrt(kappa) + FP64 error) and are rescored exactly when they
-// can reach the pool.  Rows or partners whose values leave a safe FP32 range
-// (products above LP_BIG, or a norm below LP_SMALL where subnormals would
-// matter) go to the exact fix-up.
+// the precision form's BF16 bound.  The FP32 moments (inputs rounded once,
+// n rounded additions, v = 2^-24) satisfy |dS1| <= (n+2) v sqrt(n) ||f|| and
+// |dS2| <= (n+6) v S2, so the variance moves by at most 3 (n+3) v kappa of
+// itself and the score (targets centred, unit norm) by at most cm kappa with
+// cm = 3 (n+8) v (r3_moment_err); kappa itself is then known within a
+// factor 1 +- 4/3 cm kappa, which the bound below absorbs.  Scores with
+// kappa <= LP_KAPPA are stored (error within the selection margin 1.1 delta
+// + 1.5 cm); others store the upper bound -(s + delta sqrt(kappa)(1 + cm
+// kappa) + 1.1 cm kappa) and are rescored exactly when they can reach the
+// pool.  Rows or partners whose values leave a safe FP32 range (products
+// above LP_BIG, squares above LP_BIG2, a norm below LP_SMALL2 where
+// subnormals would matter) or whose kappa makes cm kappa exceed 0.05 go to
+// the exact fix-up.
 constexpr double LP_BIG = 1e30;
-constexpr double LP_SMALL = 1e-20;
+constexpr double LP_BIG2 = 1e16;        // |f|, |g|, |x| below this: n f^2 stays finite in FP32
+constexpr double LP_SMALL2 = 1e-10;     // ||f|| above this: FP32 subnormals are negligible
 constexpr double LP_KAPPA = 1.21;
 
 typedef __attribute__((ext_vector_type(8))) __bf16 r3_bf16x8;
@@ -486,15 +494,15 @@ __device__ __forceinline__ unsigned r3_bf16_pack(float lo, float hi) {
 }
 
 // Right-hand operands of the precision form, per column tile c and 32-sample
-// chunk ch (512 entries each): b64[(c NC + ch) 512 + 128 q + 2 L + i] = x of
-// column L%16 at sample 32 ch + 8 (L/16) + 2 q + i (pairs of samples, lane
-// L's pair q contiguous across lanes, so that a 16-byte read per lane covers
-// one pair of every lane); blp[((c TP + t) NC + ch) 512 + 8 l + e] =
+// chunk ch (512 entries each): b32[(c NC + ch) 512 + 256 h + 4 L + i] =
+// FP32(x) of column L%16 at sample 32 ch + 8 (L/16) + 4 h + i (lane L's
+// half h contiguous across lanes, so that a 16-byte read per lane covers
+// one half of every lane); blp[((c TP + t) NC + ch) 512 + 8 l + e] =
 // BF16(x y_t) of column l%16 at sample 32 ch + 8 (l/16) + e.
 __global__ __launch_bounds__(256) void k_r3_bmat_lp(int n, int64_t ldn, int TP, int NC, int nct,
                                                     const int32_t* __restrict__ coldesc,
                                                     const double* __restrict__ Vf, const double* __restrict__ Rf,
-                                                    const double* __restrict__ Yn, double* __restrict__ b64,
+                                                    const double* __restrict__ Yn, float* __restrict__ b32,
                                                     __bf16* __restrict__ blp) {
     const int64_t per = (int64_t)NC * 512;
     const int64_t total = (int64_t)nct * (1 + TP) * per;
@@ -504,9 +512,9 @@ __global__ __launch_bounds__(256) void k_r3_bmat_lp(int n, int64_t ldn, int TP, 
         const int ch = (int)(r / 512), w = (int)(r % 512);
         int j, s;
         if (v == 0) {
-            const int q = w >> 7, L = (w & 127) >> 1, i = w & 1;
+            const int h = w >> 8, L = (w & 255) >> 2, i = w & 3;
             j = L & 15;
-            s = 32 * ch + 8 * (L >> 4) + 2 * q + i;
+            s = 32 * ch + 8 * (L >> 4) + 4 * h + i;
         } else {
             const int l = w >> 3, e = w & 7;
             j = l & 15;
@@ -519,7 +527,7 @@ __global__ __launch_bounds__(256) void k_r3_bmat_lp(int n, int64_t ldn, int TP, 
             x = kind == 3 ? 1.0 : kind == 1 ? Rf[(int64_t)p * ldn + s] : Vf[(int64_t)p * ldn + s];
         }
         if (v == 0) {
-            b64[(int64_t)c * per + r] = x;
+            b32[(int64_t)c * per + r] = (float)x;
         } else {
             const int t = v - 1;
             const double yv = (s < n) ? Yn[(int64_t)t * ldn + s] : 0.0;
@@ -531,15 +539,16 @@ __global__ __launch_bounds__(256) void k_r3_bmat_lp(int n, int64_t ldn, int TP, 
 
 struct R3lpArgs {
     R3mArgs m;
-    const double* b64;
+    const float* b32;
     const __bf16* blp;
     const double* r2q;        // mean square of each rung-2 feature (by id - off[2])
     int NC;
     int ct0;                  // first column tile of the launch
     double delta;
+    double cm;                // FP32-moment error coefficient (r3_moment_err)
 };
 
-typedef double r3_v2d __attribute__((ext_vector_type(2)));
+typedef float r3_f32x2 __attribute__((ext_vector_type(2)));
 
 // A block's four waves take four row tiles against one column tile; the
 // column tile's operands of a chunk (x, x^2 and the TP products x y_t: 8 +
@@ -581,32 +590,32 @@ __global__ __launch_bounds__(256, (TP <= 8 ? 2 : 1)) void k_r3_lp(R3lpArgs a) {
         rok[u] = rok[u] && g.r2v[j2[u] - g.sd.off[2]];
         r3_rows(g.Vf, g.Rf, g.ldn, op2 < OP_ADD ? -1 : (rok[u] ? k : 0), rok[u] ? l : 0, op2, p1[u], p2[u]);
     }
-    r3_v4d s1[GT], s2[GT];
+    r3_f32x4 s1[GT], s2[GT];
     r3_f32x4 pa[GT][TP];
     double hmx[GT];                                      // div tiles: max |1/g| of the lane's samples
 #pragma unroll
     for (int u = 0; u < GT; u++) {
-        s1[u] = r3_v4d{0.0, 0.0, 0.0, 0.0};
-        s2[u] = r3_v4d{0.0, 0.0, 0.0, 0.0};
+        s1[u] = r3_f32x4{0.f, 0.f, 0.f, 0.f};
+        s2[u] = r3_f32x4{0.f, 0.f, 0.f, 0.f};
         hmx[u] = 0.0;
 #pragma unroll
         for (int t = 0; t < TP; t++) pa[u][t] = r3_f32x4{0.f, 0.f, 0.f, 0.f};
     }
-    // LDS buffer: x (512 doubles, pair-major as in b64), x^2 (same), then
-    // the TP x y_t blocks (512 BF16 each, lane-major as in blp)
-    constexpr int BUF = (8 + TP) * 1024;
+    // LDS buffer: x (512 FP32, half-major as in b32), x^2 (same), then the
+    // TP x y_t blocks (512 BF16 each, lane-major as in blp)
+    constexpr int BUF = (4 + TP) * 1024;
     __shared__ __attribute__((aligned(16))) char smem[2 * BUF];
     constexpr int NPB = (TP * 64 + 255) / 256;           // 16-byte pieces of x y_t per thread
-    const double* gx = a.b64 + (int64_t)ct * a.NC * 512;
+    const float* gx = a.b32 + (int64_t)ct * a.NC * 512;
     const __bf16* gb = a.blp + (int64_t)ct * TP * a.NC * 512;
-    r3_v2d sx;
+    r3_f32x2 sx;
     r3_u32x4 sb[NPB];
     // piece i of thread tid: q = tid + 256 i (with fewer than 256 pieces,
     // threads share pieces and write the same bytes); every thread loads and
     // stores on every chunk, so that no load sits behind a branch
     auto piece = [&](int i) { return TP * 64 >= 256 ? tid + 256 * i : (tid & (TP * 64 - 1)); };
     auto stage_load = [&](int ch) {
-        sx = *(const r3_v2d*)(gx + (int64_t)ch * 512 + 2 * tid);
+        sx = *(const r3_f32x2*)(gx + (int64_t)ch * 512 + 2 * tid);
 #pragma unroll
         for (int i = 0; i < NPB; i++) {
             const int q = piece(i);
@@ -614,10 +623,10 @@ __global__ __launch_bounds__(256, (TP <= 8 ? 2 : 1)) void k_r3_lp(R3lpArgs a) {
         }
     };
     auto stage_store = [&](int buf) {
-        double* xs = (double*)(smem + buf * BUF);
-        *(r3_v2d*)(xs + 2 * tid) = sx;
-        *(r3_v2d*)(xs + 512 + 2 * tid) = sx * sx;
-        char* bs = smem + buf * BUF + 8192;
+        float* xs = (float*)(smem + buf * BUF);
+        *(r3_f32x2*)(xs + 2 * tid) = sx;
+        *(r3_f32x2*)(xs + 512 + 2 * tid) = sx * sx;
+        char* bs = smem + buf * BUF + 4096;
 #pragma unroll
         for (int i = 0; i < NPB; i++) {
             const int q = piece(i);
@@ -655,13 +664,13 @@ __global__ __launch_bounds__(256, (TP <= 8 ? 2 : 1)) void k_r3_lp(R3lpArgs a) {
         if (active) {
             const int s = 32 * ch + 8 * kq;
             const bool tail = ch == a.NC - 1;
-            const double* xs = (const double*)(smem + (ch & 1) * BUF);
-            const char* bs = smem + (ch & 1) * BUF + 8192;
-            r3_v2d xp[4], x2p[4];
+            const float* xs = (const float*)(smem + (ch & 1) * BUF);
+            const char* bs = smem + (ch & 1) * BUF + 4096;
+            r3_f32x4 xp[2], x2p[2];
 #pragma unroll
-            for (int q = 0; q < 4; q++) {
-                xp[q] = *(const r3_v2d*)(xs + 128 * q + 2 * lane);
-                x2p[q] = *(const r3_v2d*)(xs + 512 + 128 * q + 2 * lane);
+            for (int h = 0; h < 2; h++) {
+                xp[h] = *(const r3_f32x4*)(xs + 256 * h + 4 * lane);
+                x2p[h] = *(const r3_f32x4*)(xs + 512 + 256 * h + 4 * lane);
             }
 #pragma unroll
             for (int u = 0; u < GT; u++) {
@@ -689,8 +698,8 @@ __global__ __launch_bounds__(256, (TP <= 8 ? 2 : 1)) void k_r3_lp(R3lpArgs a) {
                 }
 #pragma unroll
                 for (int e = 0; e < 8; e++) {
-                    s1[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[e], xp[e >> 1][e & 1], s1[u], 0, 0, 0);
-                    s2[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[e] * v[e], x2p[e >> 1][e & 1], s2[u], 0, 0, 0);
+                    s1[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(vf[e], xp[e >> 2][e & 3], s1[u], 0, 0, 0);
+                    s2[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(vf[e] * vf[e], x2p[e >> 2][e & 3], s2[u], 0, 0, 0);
                 }
                 const r3_u32x4 au = {r3_bf16_pack(vf[0], vf[1]), r3_bf16_pack(vf[2], vf[3]),
                                      r3_bf16_pack(vf[4], vf[5]), r3_bf16_pack(vf[6], vf[7])};
@@ -721,17 +730,11 @@ __global__ __launch_bounds__(256, (TP <= 8 ? 2 : 1)) void k_r3_lp(R3lpArgs a) {
             hmx[u] = fmax(hmx[u], __shfl_xor(hmx[u], 16, 64));
             hmx[u] = fmax(hmx[u], __shfl_xor(hmx[u], 32, 64));
         }
-        // FP64 results: row kq + 4r in register r; wanted: row 4 kq + e in slot e
-        double S1[4], S2[4];
+        double S1[4], S2[4];                             // row 4 kq + e in slot e
 #pragma unroll
         for (int e = 0; e < 4; e++) {
-            S1[e] = 0.0;
-            S2[e] = 0.0;
-#pragma unroll
-            for (int r = 0; r < 4; r++) {
-                const double x1 = __shfl(s1[u][r], r16 + 16 * e, 64), x2 = __shfl(s2[u][r], r16 + 16 * e, 64);
-                if (r == kq) { S1[e] = x1; S2[e] = x2; }
-            }
+            S1[e] = (double)s1[u][e];
+            S2[e] = (double)s2[u][e];
         }
 #pragma unroll
         for (int e = 0; e < 4; e++) {
@@ -763,7 +766,8 @@ __global__ __launch_bounds__(256, (TP <= 8 ? 2 : 1)) void k_r3_lp(R3lpArgs a) {
             }
             const double varn = S2[e] - S1[e] * (S1[e] / nn);
             const double kappa = varn > 0.0 ? S2[e] / varn : INFINITY;
-            const bool lp_ok = amx < LP_BIG && fmx < LP_BIG && bmx < LP_BIG && S2[e] > LP_SMALL * LP_SMALL;
+            const bool lp_ok = amx < LP_BIG2 && fmx < LP_BIG2 && bmx < LP_BIG2 &&
+                               S2[e] > LP_SMALL2 * LP_SMALL2 && a.cm * kappa <= 0.05;
             if (!sure || !lp_ok || !(kappa <= R3_KAPPA_MAX)) {
                 const unsigned long long slot = r3_slot(g.fix_cnt);
                 if ((int64_t)slot < g.fix_cap) g.fix_ids[slot] = id;
@@ -771,7 +775,7 @@ __global__ __launch_bounds__(256, (TP <= 8 ? 2 : 1)) void k_r3_lp(R3lpArgs a) {
             }
             const double isd = 1.0 / sqrt(varn);
             const bool precise = kappa <= LP_KAPPA;
-            const double ub = a.delta * sqrt(kappa) + 4.0 * nn * 1.1102230246251565e-16 * kappa;
+            const double ub = a.delta * sqrt(kappa) * (1.0 + a.cm * kappa) + 1.1 * a.cm * kappa;
             cnt++;
             if (g.mode == DISCOVER_SCORE_MAX) {
                 double best = 0.0;
@@ -958,11 +962,11 @@ void launch_r3(discover_ctx* ctx, const R3Launch& a, hipStream_t st) {
         k_r3_pstat<<<(unsigned)P.pe, 256, 0, st>>>(a.n, a.ldn, P.pe, a.Vf, a.pstat);
         check_launch("k_r3_pstat");
         const int NC = r3_chunks(a.n);
-        double* b64 = a.bmat;
-        __bf16* blp = (__bf16*)(a.bmat + (size_t)P.n_ctiles * NC * 512);
+        float* b32 = (float*)a.bmat;
+        __bf16* blp = (__bf16*)(b32 + (size_t)P.n_ctiles * NC * 512);
         const int64_t tot = (int64_t)P.n_ctiles * (a.TP + 1) * NC * 512;
         k_r3_bmat_lp<<<(unsigned)std::min<int64_t>(cdiv(tot, 256), 16384), 256, 0, st>>>(
-            a.n, a.ldn, a.TP, NC, P.n_ctiles, P.coldesc, a.Vf, a.Rf, a.Yn, b64, blp);
+            a.n, a.ldn, a.TP, NC, P.n_ctiles, P.coldesc, a.Vf, a.Rf, a.Yn, b32, blp);
         check_launch("k_r3_bmat_lp");
         R3lpArgs l{};
         R3mArgs& m = l.m;
@@ -972,7 +976,7 @@ void launch_r3(discover_ctx* ctx, const R3Launch& a, hipStream_t st) {
         m.valid = a.valid; m.mat_raw = a.mat_raw; m.r2v = a.r2v; m.ysum = a.ysum; m.sd = a.sd;
         m.N = a.N; m.scores = a.scores; m.nscored = a.nscored; m.fix_ids = a.fix_ids;
         m.fix_cnt = a.fix_cnt; m.fix_cap = a.fix_cap;
-        l.b64 = b64; l.blp = blp; l.r2q = a.r2q; l.NC = NC; l.delta = a.delta;
+        l.b32 = b32; l.blp = blp; l.r2q = a.r2q; l.NC = NC; l.delta = a.delta; l.cm = r3_moment_err(a.n);
         KTimer kt(ctx, st, "screen_r3");
         switch (a.TP) {
         case 1: launch_lp<1, 1>(l, P.n_gct, P.n_ctiles, P.n_grec, st); break;

@@ -3417,6 +3417,9 @@ static void generate_screen_once(discover_ctx* ctx, const discover_problem* prob
         margin[b] = 4.0 * P.n * EPS64 * KAPPA_MAX;
         if (prm.precision != DISCOVER_FP64) {
             s.guard_band = lowprec_margin(prm.precision, P.n);
+            // rung 3 in BF16 carries its FP32 moments' error as well
+            if (prm.precision == DISCOVER_BF16_GUARD && P.plan->sp.stream3)
+                s.guard_band += 1.5 * r3_moment_err(P.n);
             margin[b] = std::max(margin[b], s.guard_band);
         }
     }
