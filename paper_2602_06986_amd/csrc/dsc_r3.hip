@@ -26,6 +26,7 @@
 #include <algorithm>
 #include <map>
 #include <string>
+#include <type_traits>
 
 namespace dsc {
 
@@ -543,109 +544,121 @@ struct R3lpArgs {
     const __bf16* blp;
     const double* r2q;        // mean square of each rung-2 feature (by id - off[2])
     int NC;
-    int ct0;                  // first column tile of the launch
+    int ct0, ct1;             // column tiles of the launch
     double delta;
     double cm;                // FP32-moment error coefficient (r3_moment_err)
 };
 
 typedef float r3_f32x2 __attribute__((ext_vector_type(2)));
 
-// A block's four waves take four row tiles against one column tile; the
-// column tile's operands of a chunk (x, x^2 and the TP products x y_t: 8 +
-// TP KB) are staged once per block in LDS, double-buffered, and each wave
-// reads them there (16 contiguous bytes per lane per read).  The next
-// chunk's operands are loaded into registers (a share of 16 (1 + TP/4) bytes
-// per thread) and the next chunk's row operands per wave while the current
-// chunk's products are issued.
+// A block's four waves take four row tiles (16 rung-2 features each)
+// against CT column tiles (16 partner columns each): a wave regenerates its
+// row values once per chunk and issues the products of every column tile
+// from them.  The column tiles' operands of a chunk (x, x^2 and the TP
+// products x y_t: 4 + TP KB per tile) are staged once per block in LDS,
+// double-buffered, and each wave reads them there (16 contiguous bytes per
+// lane per read).  The next chunk's operands are loaded into registers (a
+// share of 8 + 16 TP/4 bytes per tile per thread) and the next chunk's row
+// operands per wave while the current chunk's products are issued.
 // HK: the launch's column tiles multiply 1/g (div), else g (mul, rdiv);
 // the two kinds are separate launches, so that neither carries the
-// other's per-sample work.
-template <int TP, int GT, bool HK>
-__global__ __launch_bounds__(256, (TP <= 8 ? 2 : 1)) void k_r3_lp(R3lpArgs a) {
+// other's per-sample work.  Column tiles past the launch's range (the last
+// group may be short) repeat its last tile and store nothing.
+template <int TP, int CT, bool HK>
+__global__ __launch_bounds__(256, (TP * CT <= 16 ? 2 : 1)) void k_r3_lp(R3lpArgs a) {
     const R3mArgs& g = a.m;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int r16 = lane & 15, kq = lane >> 4;
     const int cb = blockIdx.x / g.n_gblk;
-    const int ct = a.ct0 + cb;
-    const int64_t tile0 = ((int64_t)(blockIdx.x - cb * g.n_gblk) * 4 + r3_wave()) * GT;
+    const int ctb = a.ct0 + cb * CT;                     // first column tile of the block
+    const int64_t tile0 = (int64_t)(blockIdx.x - cb * g.n_gblk) * 4 + r3_wave();
     // a wave without a row tile still stages its share and meets every barrier
     const bool active = tile0 * 16 < g.n_grec;
     constexpr bool hk = HK;
-    bool rok[GT];
-    int64_t j2[GT];
-    int oo[GT];
-    const double* p1[GT];
-    const double* p2[GT];
-#pragma unroll
-    for (int u = 0; u < GT; u++) {
-        const int64_t t16 = min(tile0 + u, (g.n_grec >> 4) - 1) * 16;
-        const int64_t rec = (tile0 + u) * 16 + r16;
+    bool rok;
+    int64_t j2;
+    int oo;
+    const double* p1;
+    const double* p2;
+    {
+        const int64_t t16 = min(tile0, (g.n_grec >> 4) - 1) * 16;
+        const int64_t rec = tile0 * 16 + r16;
         int k = -2, l = 0, op2;
         r3_rec(g.grec[rec < g.n_grec ? rec : t16], k, l, op2);
         op2 = __builtin_amdgcn_readfirstlane(op2);
-        oo[u] = op2;
-        rok[u] = rec < g.n_grec && k != -2;
-        j2[u] = rok[u] ? r3_j2(g.sd, g.mat_raw, k, l, op2) : 0;
-        rok[u] = rok[u] && g.r2v[j2[u] - g.sd.off[2]];
-        r3_rows(g.Vf, g.Rf, g.ldn, op2 < OP_ADD ? -1 : (rok[u] ? k : 0), rok[u] ? l : 0, op2, p1[u], p2[u]);
+        oo = op2;
+        rok = rec < g.n_grec && k != -2;
+        j2 = rok ? r3_j2(g.sd, g.mat_raw, k, l, op2) : 0;
+        rok = rok && g.r2v[j2 - g.sd.off[2]];
+        r3_rows(g.Vf, g.Rf, g.ldn, op2 < OP_ADD ? -1 : (rok ? k : 0), rok ? l : 0, op2, p1, p2);
     }
-    r3_f32x4 s1[GT], s2[GT];
-    r3_f32x4 pa[GT][TP];
-    double hmx[GT];                                      // div tiles: max |1/g| of the lane's samples
+    r3_f32x4 s1[CT], s2[CT];
+    r3_f32x4 pa[CT][TP];
+    double hmx = 0.0;                                    // div tiles: max |1/g| of the lane's samples
 #pragma unroll
-    for (int u = 0; u < GT; u++) {
-        s1[u] = r3_f32x4{0.f, 0.f, 0.f, 0.f};
-        s2[u] = r3_f32x4{0.f, 0.f, 0.f, 0.f};
-        hmx[u] = 0.0;
+    for (int c = 0; c < CT; c++) {
+        s1[c] = r3_f32x4{0.f, 0.f, 0.f, 0.f};
+        s2[c] = r3_f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int t = 0; t < TP; t++) pa[u][t] = r3_f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int t = 0; t < TP; t++) pa[c][t] = r3_f32x4{0.f, 0.f, 0.f, 0.f};
     }
-    // LDS buffer: x (512 FP32, half-major as in b32), x^2 (same), then the
-    // TP x y_t blocks (512 BF16 each, lane-major as in blp)
-    constexpr int BUF = (4 + TP) * 1024;
+    // LDS buffer: per column tile x (512 FP32, half-major as in b32), x^2
+    // (same), then the TP x y_t blocks (512 BF16 each, lane-major as in blp)
+    constexpr int TB = (4 + TP) * 1024;
+    constexpr int BUF = CT * TB;
     __shared__ __attribute__((aligned(16))) char smem[2 * BUF];
-    constexpr int NPB = (TP * 64 + 255) / 256;           // 16-byte pieces of x y_t per thread
-    const float* gx = a.b32 + (int64_t)ct * a.NC * 512;
-    const __bf16* gb = a.blp + (int64_t)ct * TP * a.NC * 512;
-    r3_f32x2 sx;
-    r3_u32x4 sb[NPB];
+    constexpr int NPB = (TP * 64 + 255) / 256;           // 16-byte pieces of x y_t per thread and tile
+    const float* gx[CT];
+    const __bf16* gb[CT];
+#pragma unroll
+    for (int c = 0; c < CT; c++) {
+        const int ctc = min(ctb + c, a.ct1 - 1);
+        gx[c] = a.b32 + (int64_t)ctc * a.NC * 512;
+        gb[c] = a.blp + (int64_t)ctc * TP * a.NC * 512;
+    }
+    r3_f32x2 sx[CT];
+    r3_u32x4 sb[CT][NPB];
     // piece i of thread tid: q = tid + 256 i (with fewer than 256 pieces,
     // threads share pieces and write the same bytes); every thread loads and
     // stores on every chunk, so that no load sits behind a branch
     auto piece = [&](int i) { return TP * 64 >= 256 ? tid + 256 * i : (tid & (TP * 64 - 1)); };
     auto stage_load = [&](int ch) {
-        sx = *(const r3_f32x2*)(gx + (int64_t)ch * 512 + 2 * tid);
 #pragma unroll
-        for (int i = 0; i < NPB; i++) {
-            const int q = piece(i);
-            sb[i] = *(const r3_u32x4*)(gb + ((int64_t)(q >> 6) * a.NC + ch) * 512 + (q & 63) * 8);
+        for (int c = 0; c < CT; c++) {
+            sx[c] = *(const r3_f32x2*)(gx[c] + (int64_t)ch * 512 + 2 * tid);
+#pragma unroll
+            for (int i = 0; i < NPB; i++) {
+                const int q = piece(i);
+                sb[c][i] = *(const r3_u32x4*)(gb[c] + ((int64_t)(q >> 6) * a.NC + ch) * 512 + (q & 63) * 8);
+            }
         }
     };
     auto stage_store = [&](int buf) {
-        float* xs = (float*)(smem + buf * BUF);
-        *(r3_f32x2*)(xs + 2 * tid) = sx;
-        *(r3_f32x2*)(xs + 512 + 2 * tid) = sx * sx;
-        char* bs = smem + buf * BUF + 4096;
 #pragma unroll
-        for (int i = 0; i < NPB; i++) {
-            const int q = piece(i);
-            *(r3_u32x4*)(bs + (q >> 6) * 1024 + (q & 63) * 16) = sb[i];
+        for (int c = 0; c < CT; c++) {
+            float* xs = (float*)(smem + buf * BUF + c * TB);
+            *(r3_f32x2*)(xs + 2 * tid) = sx[c];
+            *(r3_f32x2*)(xs + 512 + 2 * tid) = sx[c] * sx[c];
+            char* bs = smem + buf * BUF + c * TB + 4096;
+#pragma unroll
+            for (int i = 0; i < NPB; i++) {
+                const int q = piece(i);
+                *(r3_u32x4*)(bs + (q >> 6) * 1024 + (q & 63) * 16) = sb[c][i];
+            }
         }
     };
-    // row operands of chunk ch: 8 samples of two operand rows per tile
+    // row operands of chunk ch: 8 samples of two operand rows
     struct Ld {
-        r3_v4d x1[GT][2], x2[GT][2];
+        r3_v4d x1[2], x2[2];
     };
     auto load_rows = [&](int ch, Ld& L) {
         const int s = 32 * ch + 8 * kq;
 #pragma unroll
-        for (int u = 0; u < GT; u++)
-#pragma unroll
-            for (int h = 0; h < 2; h++) {
-                L.x1[u][h] = *(const r3_v4d*)(p1[u] + s + 4 * h);
-                L.x2[u][h] = *(const r3_v4d*)(p2[u] + s + 4 * h);
-            }
+        for (int h = 0; h < 2; h++) {
+            L.x1[h] = *(const r3_v4d*)(p1 + s + 4 * h);
+            L.x2[h] = *(const r3_v4d*)(p2 + s + 4 * h);
+        }
     };
     Ld cur, nxt;
     stage_load(0);
@@ -664,50 +677,50 @@ __global__ __launch_bounds__(256, (TP <= 8 ? 2 : 1)) void k_r3_lp(R3lpArgs a) {
         if (active) {
             const int s = 32 * ch + 8 * kq;
             const bool tail = ch == a.NC - 1;
-            const float* xs = (const float*)(smem + (ch & 1) * BUF);
-            const char* bs = smem + (ch & 1) * BUF + 4096;
-            r3_f32x4 xp[2], x2p[2];
+            double v[8];
 #pragma unroll
             for (int h = 0; h < 2; h++) {
-                xp[h] = *(const r3_f32x4*)(xs + 256 * h + 4 * lane);
-                x2p[h] = *(const r3_f32x4*)(xs + 512 + 256 * h + 4 * lane);
-            }
+                const r3_v4d w = r3_combine(oo, cur.x1[h], cur.x2[h]);
 #pragma unroll
-            for (int u = 0; u < GT; u++) {
-                double v[8];
+                for (int e = 0; e < 4; e++) v[4 * h + e] = w[e];
+            }
+            float vf[8], vq[8];
+#pragma unroll
+            for (int e = 0; e < 8; e++) {
+                double x = v[e];
+                if (hk) x = r3_rcp(x);
+                if (tail && s + e >= g.n) x = 0.0;
+                if (hk) hmx = fabs(x) > hmx ? fabs(x) : hmx;   // NaN leaves it unchanged
+                // FP64 -> FP32 here and FP32 -> BF16 in the pack: two
+                // hardware roundings (the error bound counts both); the
+                // empty asm keeps the compiler from fusing them into one
+                // correctly rounded (and much longer) conversion
+                vf[e] = (float)x;
+                __asm__("" : "+v"(vf[e]));
+                vq[e] = vf[e] * vf[e];
+            }
+            const r3_u32x4 au = {r3_bf16_pack(vf[0], vf[1]), r3_bf16_pack(vf[2], vf[3]),
+                                 r3_bf16_pack(vf[4], vf[5]), r3_bf16_pack(vf[6], vf[7])};
+            const r3_bf16x8 av = __builtin_bit_cast(r3_bf16x8, au);
+#pragma unroll
+            for (int c = 0; c < CT; c++) {
+                const float* xs = (const float*)(smem + (ch & 1) * BUF + c * TB);
+                const char* bs = smem + (ch & 1) * BUF + c * TB + 4096;
+                r3_f32x4 xp[2], x2p[2];
 #pragma unroll
                 for (int h = 0; h < 2; h++) {
-                    const r3_v4d w = r3_combine(oo[u], cur.x1[u][h], cur.x2[u][h]);
-#pragma unroll
-                    for (int e = 0; e < 4; e++) v[4 * h + e] = w[e];
-                }
-                float vf[8];
-#pragma unroll
-                for (int e = 0; e < 8; e++) {
-                    double x = v[e];
-                    if (hk) x = r3_rcp(x);
-                    if (tail && s + e >= g.n) x = 0.0;
-                    if (hk) hmx[u] = fabs(x) > hmx[u] ? fabs(x) : hmx[u];   // NaN leaves it unchanged
-                    v[e] = x;
-                    // FP64 -> FP32 here and FP32 -> BF16 in the pack: two
-                    // hardware roundings (the error bound counts both); the
-                    // empty asm keeps the compiler from fusing them into one
-                    // correctly rounded (and much longer) conversion
-                    vf[e] = (float)x;
-                    __asm__("" : "+v"(vf[e]));
+                    xp[h] = *(const r3_f32x4*)(xs + 256 * h + 4 * lane);
+                    x2p[h] = *(const r3_f32x4*)(xs + 512 + 256 * h + 4 * lane);
                 }
 #pragma unroll
                 for (int e = 0; e < 8; e++) {
-                    s1[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(vf[e], xp[e >> 2][e & 3], s1[u], 0, 0, 0);
-                    s2[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(vf[e] * vf[e], x2p[e >> 2][e & 3], s2[u], 0, 0, 0);
+                    s1[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(vf[e], xp[e >> 2][e & 3], s1[c], 0, 0, 0);
+                    s2[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(vq[e], x2p[e >> 2][e & 3], s2[c], 0, 0, 0);
                 }
-                const r3_u32x4 au = {r3_bf16_pack(vf[0], vf[1]), r3_bf16_pack(vf[2], vf[3]),
-                                     r3_bf16_pack(vf[4], vf[5]), r3_bf16_pack(vf[6], vf[7])};
-                const r3_bf16x8 av = __builtin_bit_cast(r3_bf16x8, au);
 #pragma unroll
                 for (int t = 0; t < TP; t++) {
                     const r3_bf16x8 bv = *(const r3_bf16x8*)(bs + t * 1024 + lane * 16);
-                    pa[u][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, pa[u][t], 0, 0, 0);
+                    pa[c][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, pa[c][t], 0, 0, 0);
                 }
             }
         }
@@ -716,32 +729,34 @@ __global__ __launch_bounds__(256, (TP <= 8 ? 2 : 1)) void k_r3_lp(R3lpArgs a) {
         cur = nxt;
     }
     if (!active) return;
-    const int32_t cd = g.coldesc[ct * 16 + r16];
-    const int p = cd & 0xFFFF, kind = cd >> 16;
-    const int op3 = kind == 0 ? OP_MUL : kind == 1 ? OP_RDIV : OP_DIV;
-    const bool colok = cd >= 0 && ((g.ops >> (op3 - OP_ADD)) & 1u) && g.valid[p];
-    const double xmx = colok ? g.pstat[p] : 0.0, xmn = colok ? g.pstat[g.pe + p] : 1.0;
-    const int64_t praw = colok ? g.mat_raw[p] : 0;
+    if (hk) {
+        hmx = fmax(hmx, __shfl_xor(hmx, 16, 64));
+        hmx = fmax(hmx, __shfl_xor(hmx, 32, 64));
+    }
     const double nn = (double)g.n;
     unsigned cnt = 0;
 #pragma unroll
-    for (int u = 0; u < GT; u++) {
-        if (hk) {
-            hmx[u] = fmax(hmx[u], __shfl_xor(hmx[u], 16, 64));
-            hmx[u] = fmax(hmx[u], __shfl_xor(hmx[u], 32, 64));
-        }
+    for (int c = 0; c < CT; c++) {
+        if (ctb + c >= a.ct1) continue;                  // repeated tile: stores nothing
+        const int ct = ctb + c;
+        const int32_t cd = g.coldesc[ct * 16 + r16];
+        const int p = cd & 0xFFFF, kind = cd >> 16;
+        const int op3 = kind == 0 ? OP_MUL : kind == 1 ? OP_RDIV : OP_DIV;
+        const bool colok = cd >= 0 && ((g.ops >> (op3 - OP_ADD)) & 1u) && g.valid[p];
+        const double xmx = colok ? g.pstat[p] : 0.0, xmn = colok ? g.pstat[g.pe + p] : 1.0;
+        const int64_t praw = colok ? g.mat_raw[p] : 0;
         double S1[4], S2[4];                             // row 4 kq + e in slot e
 #pragma unroll
         for (int e = 0; e < 4; e++) {
-            S1[e] = (double)s1[u][e];
-            S2[e] = (double)s2[u][e];
+            S1[e] = (double)s1[c][e];
+            S2[e] = (double)s2[c][e];
         }
 #pragma unroll
         for (int e = 0; e < 4; e++) {
             const int i = 4 * kq + e;                      // row of slot e
-            const bool ok = __shfl((int)rok[u], i, 64) != 0 && colok;
-            const int64_t gj = __shfl(j2[u], i, 64);
-            const double hx = hk ? __shfl(hmx[u], i, 64) : 0.0;
+            const bool ok = __shfl((int)rok, i, 64) != 0 && colok;
+            const int64_t gj = __shfl(j2, i, 64);
+            const double hx = hk ? __shfl(hmx, i, 64) : 0.0;
             if (!ok) continue;
             // max |g| <= sqrt(sum g^2) = sqrt(n E[g^2]) (E[g^2] recorded by the
             // rung-2 screen; 1 % margin for its rounding): only compared with
@@ -781,13 +796,13 @@ __global__ __launch_bounds__(256, (TP <= 8 ? 2 : 1)) void k_r3_lp(R3lpArgs a) {
                 double best = 0.0;
 #pragma unroll
                 for (int t = 0; t < TP; t++)
-                    if (t < g.T) best = fmax(best, fabs(((double)pa[u][t][e] - S1[e] * (g.ysum[t] / nn)) * isd));
+                    if (t < g.T) best = fmax(best, fabs(((double)pa[c][t][e] - S1[e] * (g.ysum[t] / nn)) * isd));
                 g.scores[id] = precise ? best : -(best + ub);
             } else {
 #pragma unroll
                 for (int t = 0; t < TP; t++)
                     if (t < g.T) {
-                        const double r = fabs(((double)pa[u][t][e] - S1[e] * (g.ysum[t] / nn)) * isd);
+                        const double r = fabs(((double)pa[c][t][e] - S1[e] * (g.ysum[t] / nn)) * isd);
                         g.scores[(int64_t)t * g.N + id] = precise ? r : -(r + ub);
                     }
             }
@@ -798,19 +813,42 @@ __global__ __launch_bounds__(256, (TP <= 8 ? 2 : 1)) void k_r3_lp(R3lpArgs a) {
 }
 
 // One launch over the mul / rdiv column tiles [0, n_gct), one over the div
-// tiles [n_gct, nct).
-template <int TP, int GT>
+// tiles [n_gct, nct); each in groups of CT tiles per block.
+template <int TP, int CT, bool HK>
+void launch_lp_range(R3lpArgs l, int ct0, int ct1, hipStream_t st) {
+    if (ct1 <= ct0) return;
+    l.ct0 = ct0;
+    l.ct1 = ct1;
+    const int64_t groups = (ct1 - ct0 + CT - 1) / CT;
+    DSC_REQUIRE((int64_t)l.m.n_gblk * groups < ((int64_t)1 << 31), "rung-3 grid too large");
+    k_r3_lp<TP, CT, HK><<<(unsigned)((int64_t)l.m.n_gblk * groups), 256, 0, st>>>(l);
+}
+
+// Column tiles per wave: up to 3 at <= 4 targets and 2 at 8 (3 tiles at 8
+// targets hold 266 VGPRs, one wave per SIMD; measured on gfx950 at 8
+// targets: 2 tiles 19.3 ms, 3 tiles 22.8 ms per dimension of the large
+// workload), as many as the range holds; the rest in smaller groups.
+template <int TP>
 void launch_lp(R3lpArgs l, int n_gct, int nct, int64_t n_grec, hipStream_t st) {
-    l.m.n_gblk = (int)((n_grec / 16 + 4 * GT - 1) / (4 * GT));
-    DSC_REQUIRE((int64_t)l.m.n_gblk * nct < ((int64_t)1 << 31), "rung-3 grid too large");
-    if (n_gct > 0) {
-        l.ct0 = 0;
-        k_r3_lp<TP, GT, false><<<(unsigned)((int64_t)l.m.n_gblk * n_gct), 256, 0, st>>>(l);
-    }
-    if (nct > n_gct) {
-        l.ct0 = n_gct;
-        k_r3_lp<TP, GT, true><<<(unsigned)((int64_t)l.m.n_gblk * (nct - n_gct)), 256, 0, st>>>(l);
-    }
+    l.m.n_gblk = (int)((n_grec / 16 + 3) / 4);
+    constexpr int CMAX = TP <= 4 ? 3 : TP <= 8 ? 2 : 1;
+    auto range = [&](int c0, int c1, auto hk) {
+        constexpr bool HK = decltype(hk)::value;
+        int c = c0;
+        if (CMAX >= 3) {
+            const int m = (c1 - c) / 3 * 3;
+            launch_lp_range<TP, 3, HK>(l, c, c + m, st);
+            c += m;
+        }
+        if (CMAX >= 2) {
+            const int m = (c1 - c) / 2 * 2;
+            launch_lp_range<TP, 2, HK>(l, c, c + m, st);
+            c += m;
+        }
+        launch_lp_range<TP, 1, HK>(l, c, c1, st);
+    };
+    range(0, n_gct, std::false_type{});
+    range(n_gct, nct, std::true_type{});
 }
 
 template <class T>
@@ -979,11 +1017,11 @@ void launch_r3(discover_ctx* ctx, const R3Launch& a, hipStream_t st) {
         l.b32 = b32; l.blp = blp; l.r2q = a.r2q; l.NC = NC; l.delta = a.delta; l.cm = r3_moment_err(a.n);
         KTimer kt(ctx, st, "screen_r3");
         switch (a.TP) {
-        case 1: launch_lp<1, 1>(l, P.n_gct, P.n_ctiles, P.n_grec, st); break;
-        case 2: launch_lp<2, 1>(l, P.n_gct, P.n_ctiles, P.n_grec, st); break;
-        case 4: launch_lp<4, 1>(l, P.n_gct, P.n_ctiles, P.n_grec, st); break;
-        case 8: launch_lp<8, 1>(l, P.n_gct, P.n_ctiles, P.n_grec, st); break;
-        default: launch_lp<16, 1>(l, P.n_gct, P.n_ctiles, P.n_grec, st); break;
+        case 1: launch_lp<1>(l, P.n_gct, P.n_ctiles, P.n_grec, st); break;
+        case 2: launch_lp<2>(l, P.n_gct, P.n_ctiles, P.n_grec, st); break;
+        case 4: launch_lp<4>(l, P.n_gct, P.n_ctiles, P.n_grec, st); break;
+        case 8: launch_lp<8>(l, P.n_gct, P.n_ctiles, P.n_grec, st); break;
+        default: launch_lp<16>(l, P.n_gct, P.n_ctiles, P.n_grec, st); break;
         }
         check_launch("k_r3_lp");
     } else if (P.n_grec && P.n_ctiles) {
