@@ -29,7 +29,8 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP64 = 78.6e12          # MI355X FP64 vector, FLOP/s
+PEAK_FP64 = 78.6e12          # MI355X FP64 (vector and matrix), FLOP/s
+PEAK_BF16_MFMA = 2.5e15      # MI355X dense BF16 matrix, FLOP/s
 # Work per 3-subset of the D = 3 scan, counted as the Schur-complement update
 # of a 3x3 correlation system: 12 flop (and one division, not counted).
 L0_FLOP_PER_SUBSET = 12
@@ -455,22 +456,26 @@ def large_main(args):
         all([x[0] for x in ma] == [x[0] for x in mb] for ma, mb in zip(models, models64)) and \
         omp[0] == omp64[0]
     # dominant kernel of the step: the rung-3 screen.  Algorithmic work per
-    # unit-valid rung-3 candidate and sample: the FP64 sums S1 and S2 (4 flop,
-    # on the FP64 matrix cores) in the precision form; (4 + 2T) flop for FP64
-    # screening (operator, sum, sum of squares, T products with the targets).
+    # unit-valid rung-3 candidate and sample: the sum S1, the sum of squares
+    # S2 and the T products with the targets, (4 + 2T) flop.  The precision
+    # form issues all of it on the BF16 matrix cores (S1 and S2 as three
+    # split products each, 12 + 2T flop executed), so its peak is the dense
+    # BF16 matrix peak; the FP64 form issues it on the FP64 matrix cores.
     valid3 = 116840512
     Ts = [1] + [m] * (D - 1)
     roof = roof64 = None
     if "screen_r3" in kern:
         r3 = kern["screen_r3"]
-        flops = sum(valid3 * w["n"] * 4 for _ in Ts) / r3["launches_per_step"]
+        flops = sum(valid3 * w["n"] * (4 + 2 * T) for T in Ts) / r3["launches_per_step"]
         ach = flops / (r3["avg_launch_ms"] * 1e-3)
-        roof = {"kernel": "k_r3_lp (rung-3 screen, precision form)", "bound": "mfma",
-                "achieved": ach / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
-                "frac": ach / PEAK_FP64, "traffic": r3_traffic("k_r3_lp"),
+        roof = {"kernel": "k_r3_lp (rung-3 screen, precision form; one launch = the kernels of one dimension)",
+                "bound": "mfma", "achieved": ach / 1e12, "peak": PEAK_BF16_MFMA / 1e12, "unit": "TFLOP/s",
+                "frac": ach / PEAK_BF16_MFMA, "traffic": r3_traffic("k_r3_lp"),
                 "avg_launch_ms": r3["avg_launch_ms"], "launches_timed": r3["launches_per_step"] * args.steps,
-                "work": "4 n FP64 flop (S1, S2) per unit-valid rung-3 candidate per launch-average "
-                        "dimension; BF16 numerators (2 T n flop) not counted"}
+                "work": "(4 + 2T) n flop per unit-valid rung-3 candidate and launch-average dimension "
+                        "(T = 1, 8, 8), all on the BF16 matrix cores (12 + 2T n executed: split moments)",
+                "note": "the matrix cores are not what holds this kernel: it spends its time on "
+                        "regenerating rung-2 rows from rung-1 operand rows (loads and vector work)"}
     if "screen_r3" in res["fp64"][2]:
         r3 = res["fp64"][2]["screen_r3"]
         flops = sum(valid3 * w["n"] * (4 + 2 * T) for T in Ts) / r3["launches_per_step"]

@@ -50,9 +50,10 @@ std::shared_ptr<R3Plan> build_r3_plan(const Space& sp, uint32_t r3_ops);
 // Per-call buffers of one problem's rung-3 screen.
 inline int r3_quads(int n) { return 4 * (int)((n + 15) / 16); }
 inline int r3_chunks(int n) { return (int)((n + 31) / 32); }
-// Error coefficient of the precision form's FP32 moments: the score of a
-// rung-3 candidate moves by at most cm kappa through them (3 (n + 8) 2^-24).
-inline double r3_moment_err(int n) { return 3.0 * (n + 8) * 5.9604644775390625e-8; }
+// Error coefficient of the precision form's split-BF16 moments: the score
+// of a rung-3 candidate moves by at most cm kappa through them
+// (3 ((n + 50) 2^-24 + 3 2^-16)).
+inline double r3_moment_err(int n) { return 3.0 * ((n + 50) * 5.9604644775390625e-8 + 3.0 * 1.52587890625e-5); }
 // The main tiles' operands (FP64 layout, or the precision form's), then the
 // add/sub tiles' (FP64 layout) at r3_as_offset bytes.
 inline size_t r3_as_offset(const R3Plan& p, int TP, int n) {

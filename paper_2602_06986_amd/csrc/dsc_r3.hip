@@ -448,32 +448,37 @@ __global__ __launch_bounds__(256) void k_r3_mm(R3mArgs g) {
 }
 
 // ------------------------------------------------------------ precision form
-// BF16 numerators, FP32 moments.  Per 32-sample chunk a lane regenerates 8
-// consecutive samples of its row (rows 16 rung-2 features, as above) in
-// FP64 and rounds them to FP32.  S1 and S2 come from 8 + 8
-// v_mfma_f32_16x16x4f32 against [x | x^2] in FP32 (sample 8(l/16) + e of
-// the chunk in MFMA e); the T numerators from one v_mfma_f32_16x16x32_bf16
-// each against x y_t rounded to BF16 (lane l supplies row l%16 at samples
-// 8(l/16)..+7 and column l%16 at the same samples).  Every product lands in
-// the same layout: lane l holds D[4(l/16)+e][l%16] in slot e.
+// BF16 numerators, split-BF16 moments.  Per 32-sample chunk a lane
+// regenerates 8 consecutive samples of its row (rows 16 rung-2 features, as
+// above) in FP64 and rounds them to FP32 (a) and BF16 (a_h).  Every product
+// is a v_mfma_f32_16x16x32_bf16 (lane l supplies row l%16 at samples
+// 8(l/16)..+7 of the chunk and column l%16 at the same samples, and
+// receives D[4(l/16)+e][l%16] in slot e): the T numerators against x y_t
+// rounded to BF16, and the moments S1 = sum a x and S2 = sum a^2 x^2 each
+// from three products of two-term splits a = a_h + a_l (a_h = BF16(a), a_l
+// = BF16(a - a_h)): a_h x_h + (a_h x_l + a_l x_h), the cross terms in an
+// accumulator of their own.
 //
 // Error: with u = 2^-8 (plus the FP64 -> FP32 -> BF16 double rounding) the
 // product of two rounded values is within 2u + u^2 of the true product and
 // the FP32 sum adds gamma_n, so |P_lp - P| <= delta ||f|| ||y_t|| and
 // |r_lp - r| <= delta sqrt(kappa) with kappa = S2 / (S2 - S1^2/n): delta is
-// the precision form's BF16 bound.  The FP32 moments (inputs rounded once,
-// n rounded additions, v = 2^-24) satisfy |dS1| <= (n+2) v sqrt(n) ||f|| and
-// |dS2| <= (n+6) v S2, so the variance moves by at most 3 (n+3) v kappa of
-// itself and the score (targets centred, unit norm) by at most cm kappa with
-// cm = 3 (n+8) v (r3_moment_err); kappa itself is then known within a
-// factor 1 +- 4/3 cm kappa, which the bound below absorbs.  Scores with
-// kappa <= LP_KAPPA are stored (error within the selection margin 1.1 delta
-// + 1.5 cm); others store the upper bound -(s + delta sqrt(kappa)(1 + cm
-// kappa) + 1.1 cm kappa) and are rescored exactly when they can reach the
-// pool.  Rows or partners whose values leave a safe FP32 range (products
-// above LP_BIG, squares above LP_BIG2, a norm below LP_SMALL2 where
-// subnormals would matter) or whose kappa makes cm kappa exceed 0.05 go to
-// the exact fix-up.
+// the precision form's BF16 bound.  A split product misses a_l x_l and the
+// splits' own rounding: within 3 2^-16 of a x (plus the FP32 roundings of a,
+// x, a^2 and x^2, 8 v, v = 2^-24); the FP32 accumulation adds at most
+// (n + 42) v of the summed magnitudes (at most 31 roundings inside one
+// product's 32-term sum, one per accumulation).  So |dS1| <= e sqrt(n)
+// ||f|| and |dS2| <= e S2 with e = (n + 50) v + 3 2^-16, the variance moves
+// by at most 3 e kappa of itself and the score (targets centred, unit norm)
+// by at most cm kappa with cm = 3 e (r3_moment_err); kappa itself is then
+// known within a factor 1 +- 4/3 cm kappa, which the bound below absorbs.
+// Scores with kappa <= LP_KAPPA are stored (error within the selection
+// margin 1.1 delta + 1.5 cm); others store the upper bound -(s + delta
+// sqrt(kappa)(1 + cm kappa) + 1.1 cm kappa) and are rescored exactly when
+// they can reach the pool.  Rows or partners whose values leave a safe FP32
+// range (products above LP_BIG, squares above LP_BIG2, a norm below
+// LP_SMALL2 where subnormals would matter) or whose kappa makes cm kappa
+// exceed 0.05 go to the exact fix-up.
 constexpr double LP_BIG = 1e30;
 constexpr double LP_BIG2 = 1e16;        // |f|, |g|, |x| below this: n f^2 stays finite in FP32
 constexpr double LP_SMALL2 = 1e-10;     // ||f|| above this: FP32 subnormals are negligible
@@ -494,12 +499,19 @@ __device__ __forceinline__ unsigned r3_bf16_pack(float lo, float hi) {
     return __builtin_bit_cast(unsigned, v);
 }
 
+// Two-term BF16 splits of two FP32 values: hi = their BF16 roundings
+// (packed as r3_bf16_pack), lo = the BF16 roundings of the exact remainders
+// v - hi.
+__device__ __forceinline__ void r3_split(float v0, float v1, unsigned& hi, unsigned& lo) {
+    hi = r3_bf16_pack(v0, v1);
+    const float h0 = __uint_as_float(hi << 16), h1 = __uint_as_float(hi & 0xFFFF0000u);
+    lo = r3_bf16_pack(v0 - h0, v1 - h1);
+}
+
 // Right-hand operands of the precision form, per column tile c and 32-sample
-// chunk ch (512 entries each): b32[(c NC + ch) 512 + 256 h + 4 L + i] =
-// FP32(x) of column L%16 at sample 32 ch + 8 (L/16) + 4 h + i (lane L's
-// half h contiguous across lanes, so that a 16-byte read per lane covers
-// one half of every lane); blp[((c TP + t) NC + ch) 512 + 8 l + e] =
-// BF16(x y_t) of column l%16 at sample 32 ch + 8 (l/16) + e.
+// chunk ch (512 entries each, lane-major: entry 8 l + e belongs to column
+// l%16 at sample 32 ch + 8 (l/16) + e): b32[(c NC + ch) 512 + 8 l + e] =
+// FP32(x), blp[((c TP + t) NC + ch) 512 + 8 l + e] = BF16(x y_t).
 __global__ __launch_bounds__(256) void k_r3_bmat_lp(int n, int64_t ldn, int TP, int NC, int nct,
                                                     const int32_t* __restrict__ coldesc,
                                                     const double* __restrict__ Vf, const double* __restrict__ Rf,
@@ -511,16 +523,8 @@ __global__ __launch_bounds__(256) void k_r3_bmat_lp(int n, int64_t ldn, int TP, 
         const int64_t r = f % per, ck = f / per;
         const int c = (int)(ck / (1 + TP)), v = (int)(ck % (1 + TP));
         const int ch = (int)(r / 512), w = (int)(r % 512);
-        int j, s;
-        if (v == 0) {
-            const int h = w >> 8, L = (w & 255) >> 2, i = w & 3;
-            j = L & 15;
-            s = 32 * ch + 8 * (L >> 4) + 4 * h + i;
-        } else {
-            const int l = w >> 3, e = w & 7;
-            j = l & 15;
-            s = 32 * ch + 8 * (l >> 4) + e;
-        }
+        const int l = w >> 3, e = w & 7;
+        const int j = l & 15, s = 32 * ch + 8 * (l >> 4) + e;
         const int32_t d = coldesc[c * 16 + j];
         double x = 0.0;
         if (d >= 0 && s < n) {
@@ -593,18 +597,21 @@ __global__ __launch_bounds__(256, (TP * CT <= 16 ? 2 : 1)) void k_r3_lp(R3lpArgs
         rok = rok && g.r2v[j2 - g.sd.off[2]];
         r3_rows(g.Vf, g.Rf, g.ldn, op2 < OP_ADD ? -1 : (rok ? k : 0), rok ? l : 0, op2, p1, p2);
     }
-    r3_f32x4 s1[CT], s2[CT];
+    r3_f32x4 s1[CT], s2[CT], c1[CT], c2[CT];              // moments: a_h x_h and cross terms
     r3_f32x4 pa[CT][TP];
     double hmx = 0.0;                                    // div tiles: max |1/g| of the lane's samples
 #pragma unroll
     for (int c = 0; c < CT; c++) {
         s1[c] = r3_f32x4{0.f, 0.f, 0.f, 0.f};
         s2[c] = r3_f32x4{0.f, 0.f, 0.f, 0.f};
+        c1[c] = r3_f32x4{0.f, 0.f, 0.f, 0.f};
+        c2[c] = r3_f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int t = 0; t < TP; t++) pa[c][t] = r3_f32x4{0.f, 0.f, 0.f, 0.f};
     }
-    // LDS buffer: per column tile x (512 FP32, half-major as in b32), x^2
-    // (same), then the TP x y_t blocks (512 BF16 each, lane-major as in blp)
+    // LDS buffer: per column tile the splits x_h, x_l, (x^2)_h, (x^2)_l
+    // (512 BF16 each), then the TP x y_t blocks (512 BF16 each), all
+    // lane-major as in b32 and blp
     constexpr int TB = (4 + TP) * 1024;
     constexpr int BUF = CT * TB;
     __shared__ __attribute__((aligned(16))) char smem[2 * BUF];
@@ -637,9 +644,18 @@ __global__ __launch_bounds__(256, (TP * CT <= 16 ? 2 : 1)) void k_r3_lp(R3lpArgs
     auto stage_store = [&](int buf) {
 #pragma unroll
         for (int c = 0; c < CT; c++) {
-            float* xs = (float*)(smem + buf * BUF + c * TB);
-            *(r3_f32x2*)(xs + 2 * tid) = sx[c];
-            *(r3_f32x2*)(xs + 512 + 2 * tid) = sx[c] * sx[c];
+            // thread tid holds entries 2 tid, 2 tid + 1: one 4-byte BF16 pair
+            // per split
+            char* xs = smem + buf * BUF + c * TB + 4 * tid;
+            const float x0 = sx[c].x, x1 = sx[c].y;
+            const float q0 = x0 * x0, q1 = x1 * x1;
+            unsigned hi, lo;
+            r3_split(x0, x1, hi, lo);
+            *(unsigned*)xs = hi;
+            *(unsigned*)(xs + 1024) = lo;
+            r3_split(q0, q1, hi, lo);
+            *(unsigned*)(xs + 2048) = hi;
+            *(unsigned*)(xs + 3072) = lo;
             char* bs = smem + buf * BUF + c * TB + 4096;
 #pragma unroll
             for (int i = 0; i < NPB; i++) {
@@ -684,7 +700,7 @@ __global__ __launch_bounds__(256, (TP * CT <= 16 ? 2 : 1)) void k_r3_lp(R3lpArgs
 #pragma unroll
                 for (int e = 0; e < 4; e++) v[4 * h + e] = w[e];
             }
-            float vf[8], vq[8];
+            float vf[8];
 #pragma unroll
             for (int e = 0; e < 8; e++) {
                 double x = v[e];
@@ -697,26 +713,36 @@ __global__ __launch_bounds__(256, (TP * CT <= 16 ? 2 : 1)) void k_r3_lp(R3lpArgs
                 // correctly rounded (and much longer) conversion
                 vf[e] = (float)x;
                 __asm__("" : "+v"(vf[e]));
-                vq[e] = vf[e] * vf[e];
             }
-            const r3_u32x4 au = {r3_bf16_pack(vf[0], vf[1]), r3_bf16_pack(vf[2], vf[3]),
-                                 r3_bf16_pack(vf[4], vf[5]), r3_bf16_pack(vf[6], vf[7])};
-            const r3_bf16x8 av = __builtin_bit_cast(r3_bf16x8, au);
+            // av = a_h (also the numerators' operand), al = a_l, qh / ql:
+            // the splits of a^2
+            r3_u32x4 ah, al, qh, ql;
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                unsigned h, l;
+                r3_split(vf[2 * e], vf[2 * e + 1], h, l);
+                ah[e] = h;
+                al[e] = l;
+                r3_split(vf[2 * e] * vf[2 * e], vf[2 * e + 1] * vf[2 * e + 1], h, l);
+                qh[e] = h;
+                ql[e] = l;
+            }
+            const r3_bf16x8 av = __builtin_bit_cast(r3_bf16x8, ah);
+            const r3_bf16x8 avl = __builtin_bit_cast(r3_bf16x8, al);
+            const r3_bf16x8 aq = __builtin_bit_cast(r3_bf16x8, qh);
+            const r3_bf16x8 aql = __builtin_bit_cast(r3_bf16x8, ql);
 #pragma unroll
             for (int c = 0; c < CT; c++) {
-                const float* xs = (const float*)(smem + (ch & 1) * BUF + c * TB);
+                const char* xs = smem + (ch & 1) * BUF + c * TB + 16 * lane;
                 const char* bs = smem + (ch & 1) * BUF + c * TB + 4096;
-                r3_f32x4 xp[2], x2p[2];
-#pragma unroll
-                for (int h = 0; h < 2; h++) {
-                    xp[h] = *(const r3_f32x4*)(xs + 256 * h + 4 * lane);
-                    x2p[h] = *(const r3_f32x4*)(xs + 512 + 256 * h + 4 * lane);
-                }
-#pragma unroll
-                for (int e = 0; e < 8; e++) {
-                    s1[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(vf[e], xp[e >> 2][e & 3], s1[c], 0, 0, 0);
-                    s2[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(vq[e], x2p[e >> 2][e & 3], s2[c], 0, 0, 0);
-                }
+                const r3_bf16x8 xh = *(const r3_bf16x8*)xs, xl = *(const r3_bf16x8*)(xs + 1024);
+                const r3_bf16x8 x2h = *(const r3_bf16x8*)(xs + 2048), x2l = *(const r3_bf16x8*)(xs + 3072);
+                s1[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, xh, s1[c], 0, 0, 0);
+                s2[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aq, x2h, s2[c], 0, 0, 0);
+                c1[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, xl, c1[c], 0, 0, 0);
+                c2[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aq, x2l, c2[c], 0, 0, 0);
+                c1[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(avl, xh, c1[c], 0, 0, 0);
+                c2[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aql, x2h, c2[c], 0, 0, 0);
 #pragma unroll
                 for (int t = 0; t < TP; t++) {
                     const r3_bf16x8 bv = *(const r3_bf16x8*)(bs + t * 1024 + lane * 16);
@@ -748,8 +774,8 @@ __global__ __launch_bounds__(256, (TP * CT <= 16 ? 2 : 1)) void k_r3_lp(R3lpArgs
         double S1[4], S2[4];                             // row 4 kq + e in slot e
 #pragma unroll
         for (int e = 0; e < 4; e++) {
-            S1[e] = (double)s1[c][e];
-            S2[e] = (double)s2[c][e];
+            S1[e] = (double)s1[c][e] + (double)c1[c][e];
+            S2[e] = (double)s2[c][e] + (double)c2[c][e];
         }
 #pragma unroll
         for (int e = 0; e < 4; e++) {
@@ -835,12 +861,12 @@ void launch_lp(R3lpArgs l, int n_gct, int nct, int64_t n_grec, hipStream_t st) {
     auto range = [&](int c0, int c1, auto hk) {
         constexpr bool HK = decltype(hk)::value;
         int c = c0;
-        if (CMAX >= 3) {
+        if constexpr (CMAX >= 3) {
             const int m = (c1 - c) / 3 * 3;
             launch_lp_range<TP, 3, HK>(l, c, c + m, st);
             c += m;
         }
-        if (CMAX >= 2) {
+        if constexpr (CMAX >= 2) {
             const int m = (c1 - c) / 2 * 2;
             launch_lp_range<TP, 2, HK>(l, c, c + m, st);
             c += m;
