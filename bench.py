@@ -51,12 +51,13 @@ SWEEP3_COUNTERS = {
 # (KiB per dispatch) scaled by what the same counters read for a plain 1 GiB
 # device copy.  Valid only for the kernel source they were taken on.
 R3_COUNTERS = {
+    # the precision form: totals of the k_r3_lp kernels of one dimension
     "k_r3_lp": {"source": "paper_2602_06986_amd/csrc/dsc_r3.hip",
-                "sha256": "4048ecd8c0ceb2027177e2553b791c21d653ac704a1d0d37919aa30fbfa0a04d",
-                "fetch_kib": 36648076.8, "fetch_scale": 1.99992, "write_kib": 1315454.6, "write_scale": 1.0},
+                "sha256": "de9a0192ea6f3e4a00da4d60ce7d8f6af1a8761c666965edcd616289c4a7d24c",
+                "fetch_kib": 19366297.4, "fetch_scale": 1.99992, "write_kib": 1505145.6, "write_scale": 1.0},
     "k_r3_mm": {"source": "paper_2602_06986_amd/csrc/dsc_r3.hip",
-                "sha256": "4048ecd8c0ceb2027177e2553b791c21d653ac704a1d0d37919aa30fbfa0a04d",
-                "fetch_kib": 26298420.9, "fetch_scale": 1.99992, "write_kib": 1302629.0, "write_scale": 1.0},
+                "sha256": "de9a0192ea6f3e4a00da4d60ce7d8f6af1a8761c666965edcd616289c4a7d24c",
+                "fetch_kib": 23409671.7, "fetch_scale": 1.99992, "write_kib": 1300214.4, "write_scale": 1.0},
 }
 
 

@@ -504,6 +504,7 @@ __device__ __forceinline__ unsigned r3_bf16_pack(float lo, float hi) {
 // v - hi.
 __device__ __forceinline__ void r3_split(float v0, float v1, unsigned& hi, unsigned& lo) {
     hi = r3_bf16_pack(v0, v1);
+    __asm__("" : "+v"(hi));              // (the compiler would otherwise convert v0 twice)
     const float h0 = __uint_as_float(hi << 16), h1 = __uint_as_float(hi & 0xFFFF0000u);
     lo = r3_bf16_pack(v0 - h0, v1 - h1);
 }
@@ -685,75 +686,78 @@ __global__ __launch_bounds__(256, (TP * CT <= 16 ? 2 : 1)) void k_r3_lp(R3lpArgs
     // to 0 (the right-hand operands are 0 too, but a row value there may be
     // inf or NaN).  A row whose feature is invalid only reaches its own row
     // of the products, whose scores are never stored, so it is not masked.
-    // (the last chunk reloads itself into the idle buffer: unused)
-    for (int ch = 0; ch < a.NC; ch++) {
-        const int cn = ch + 1 < a.NC ? ch + 1 : ch;
-        stage_load(cn);
-        load_rows(cn, nxt);
-        if (active) {
-            const int s = 32 * ch + 8 * kq;
-            const bool tail = ch == a.NC - 1;
-            double v[8];
+    // The products of chunk ch from buffer ch & 1 and the rows in cur; the
+    // last chunk (samples >= n masked) runs after the loop as a copy of its
+    // own, so that no other chunk carries the mask.
+    auto chunk = [&](int ch, auto tail_c) {
+        constexpr bool tail = decltype(tail_c)::value;
+        const int s = 32 * ch + 8 * kq;
+        double v[8];
 #pragma unroll
-            for (int h = 0; h < 2; h++) {
-                const r3_v4d w = r3_combine(oo, cur.x1[h], cur.x2[h]);
+        for (int h = 0; h < 2; h++) {
+            const r3_v4d w = r3_combine(oo, cur.x1[h], cur.x2[h]);
 #pragma unroll
-                for (int e = 0; e < 4; e++) v[4 * h + e] = w[e];
-            }
-            float vf[8];
+            for (int e = 0; e < 4; e++) v[4 * h + e] = w[e];
+        }
+        float vf[8];
 #pragma unroll
-            for (int e = 0; e < 8; e++) {
-                double x = v[e];
-                if (hk) x = r3_rcp(x);
-                if (tail && s + e >= g.n) x = 0.0;
-                if (hk) hmx = fabs(x) > hmx ? fabs(x) : hmx;   // NaN leaves it unchanged
-                // FP64 -> FP32 here and FP32 -> BF16 in the pack: two
-                // hardware roundings (the error bound counts both); the
-                // empty asm keeps the compiler from fusing them into one
-                // correctly rounded (and much longer) conversion
-                vf[e] = (float)x;
-                __asm__("" : "+v"(vf[e]));
-            }
-            // av = a_h (also the numerators' operand), al = a_l, qh / ql:
-            // the splits of a^2
-            r3_u32x4 ah, al, qh, ql;
+        for (int e = 0; e < 8; e++) {
+            double x = v[e];
+            if (hk) x = r3_rcp(x);
+            if (tail && s + e >= g.n) x = 0.0;
+            if (hk) hmx = fabs(x) > hmx ? fabs(x) : hmx;   // NaN leaves it unchanged
+            // FP64 -> FP32 here and FP32 -> BF16 in the pack: two
+            // hardware roundings (the error bound counts both); the
+            // empty asm keeps the compiler from fusing them into one
+            // correctly rounded (and much longer) conversion
+            vf[e] = (float)x;
+            __asm__("" : "+v"(vf[e]));
+        }
+        // av = a_h (also the numerators' operand), al = a_l, qh / ql:
+        // the splits of a^2
+        r3_u32x4 ah, al, qh, ql;
 #pragma unroll
-            for (int e = 0; e < 4; e++) {
-                unsigned h, l;
-                r3_split(vf[2 * e], vf[2 * e + 1], h, l);
-                ah[e] = h;
-                al[e] = l;
-                r3_split(vf[2 * e] * vf[2 * e], vf[2 * e + 1] * vf[2 * e + 1], h, l);
-                qh[e] = h;
-                ql[e] = l;
-            }
-            const r3_bf16x8 av = __builtin_bit_cast(r3_bf16x8, ah);
-            const r3_bf16x8 avl = __builtin_bit_cast(r3_bf16x8, al);
-            const r3_bf16x8 aq = __builtin_bit_cast(r3_bf16x8, qh);
-            const r3_bf16x8 aql = __builtin_bit_cast(r3_bf16x8, ql);
+        for (int e = 0; e < 4; e++) {
+            unsigned h, l;
+            r3_split(vf[2 * e], vf[2 * e + 1], h, l);
+            ah[e] = h;
+            al[e] = l;
+            r3_split(vf[2 * e] * vf[2 * e], vf[2 * e + 1] * vf[2 * e + 1], h, l);
+            qh[e] = h;
+            ql[e] = l;
+        }
+        const r3_bf16x8 av = __builtin_bit_cast(r3_bf16x8, ah);
+        const r3_bf16x8 avl = __builtin_bit_cast(r3_bf16x8, al);
+        const r3_bf16x8 aq = __builtin_bit_cast(r3_bf16x8, qh);
+        const r3_bf16x8 aql = __builtin_bit_cast(r3_bf16x8, ql);
 #pragma unroll
-            for (int c = 0; c < CT; c++) {
-                const char* xs = smem + (ch & 1) * BUF + c * TB + 16 * lane;
-                const char* bs = smem + (ch & 1) * BUF + c * TB + 4096;
-                const r3_bf16x8 xh = *(const r3_bf16x8*)xs, xl = *(const r3_bf16x8*)(xs + 1024);
-                const r3_bf16x8 x2h = *(const r3_bf16x8*)(xs + 2048), x2l = *(const r3_bf16x8*)(xs + 3072);
-                s1[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, xh, s1[c], 0, 0, 0);
-                s2[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aq, x2h, s2[c], 0, 0, 0);
-                c1[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, xl, c1[c], 0, 0, 0);
-                c2[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aq, x2l, c2[c], 0, 0, 0);
-                c1[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(avl, xh, c1[c], 0, 0, 0);
-                c2[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aql, x2h, c2[c], 0, 0, 0);
+        for (int c = 0; c < CT; c++) {
+            const char* xs = smem + (ch & 1) * BUF + c * TB + 16 * lane;
+            const char* bs = smem + (ch & 1) * BUF + c * TB + 4096;
+            const r3_bf16x8 xh = *(const r3_bf16x8*)xs, xl = *(const r3_bf16x8*)(xs + 1024);
+            const r3_bf16x8 x2h = *(const r3_bf16x8*)(xs + 2048), x2l = *(const r3_bf16x8*)(xs + 3072);
+            s1[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, xh, s1[c], 0, 0, 0);
+            s2[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aq, x2h, s2[c], 0, 0, 0);
+            c1[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, xl, c1[c], 0, 0, 0);
+            c2[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aq, x2l, c2[c], 0, 0, 0);
+            c1[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(avl, xh, c1[c], 0, 0, 0);
+            c2[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aql, x2h, c2[c], 0, 0, 0);
 #pragma unroll
-                for (int t = 0; t < TP; t++) {
-                    const r3_bf16x8 bv = *(const r3_bf16x8*)(bs + t * 1024 + lane * 16);
-                    pa[c][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, pa[c][t], 0, 0, 0);
-                }
+            for (int t = 0; t < TP; t++) {
+                const r3_bf16x8 bv = *(const r3_bf16x8*)(bs + t * 1024 + lane * 16);
+                pa[c][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, pa[c][t], 0, 0, 0);
             }
         }
+    };
+    for (int ch = 0; ch + 1 < a.NC; ch++) {
+        stage_load(ch + 1);
+        load_rows(ch + 1, nxt);
+        if (active) chunk(ch, std::false_type{});
         stage_store((ch + 1) & 1);
         __syncthreads();
         cur = nxt;
     }
+    if (active) chunk(a.NC - 1, std::true_type{});
     if (!active) return;
     if (hk) {
         hmx = fmax(hmx, __shfl_xor(hmx, 16, 64));
