@@ -1444,6 +1444,13 @@ __device__ __forceinline__ bool rules_pass(const RuleTab& R, const Cand& c) {
     return true;
 }
 
+// Exact scores of the pool, four entries per block (one per wave) in step:
+// the first pass (values, mean, finiteness) per wave; in the second the
+// block stages the centred targets of each 64-sample chunk in LDS once
+// (double-buffered, one barrier per chunk) and every wave reads them there,
+// so the T target rows are read from memory once per four entries instead
+// of once per entry.  Per entry the arithmetic (and its order) is that of
+// wave_exact_r.
 template <int TMAX>
 __device__ __forceinline__ void d_rescore(const int64_t* __restrict__ pool,
                                                  const unsigned long long* __restrict__ Pp, int64_t cap,
@@ -1461,17 +1468,83 @@ __device__ __forceinline__ void d_rescore(const int64_t* __restrict__ pool,
                                                  const PoolVals pvs, const RuleTab* __restrict__ rules) {
     const int64_t P = min((int64_t)*Pp, cap);
     const int lane = threadIdx.x & 63;
-    for (int64_t w = (int64_t)blockIdx.x * 4 + wave_id(); w < P; w += (int64_t)gridDim.x * 4) {
-    const int64_t id = pool[w];
+    __shared__ double ys[2][TMAX][64];
+    for (int64_t g = blockIdx.x; g * 4 < P; g += gridDim.x) {      // uniform over the block
+    const int64_t w = g * 4 + wave_id();
+    const bool has = w < P;
+    const int64_t id = has ? pool[w] : 0;
     Cand c;
-    bool ok = cand_of_id(ev, id, c);
+    bool ok = has && cand_of_id(ev, id, c);
     // a candidate the rules do not allow keeps its values but is never selected
     const bool allowed = !ok || !rules || rules_pass(*rules, c);
+    const bool keep = has && w < pvs.cap;
+    double* vals = keep ? pvs.v + w * pvs.ld : nullptr;
+    // first pass: values, mean, finiteness, add/sub cancellation
+    double m = 0.0;
+    if (ok) {
+        double s = 0.0;
+        int bad = 0;
+        const bool addsub = (c.kind == 2 || c.kind == 3) && (c.op == OP_ADD || c.op == OP_SUB);
+        double ff = 0.0, ab = 0.0;
+        for (int i = lane; i < n; i += 64) {
+            const double f = cand_value(c, o, i);
+            bad |= !isfinite(f);
+            s += f;
+            if (vals) vals[i] = f;
+            if (addsub) {
+                const double a = o.Vf[(int64_t)c.ca * o.ldn + i];
+                double b;
+                if (c.kind == 2) b = o.Vf[(int64_t)c.cb * o.ldn + i];
+                else b = c.cd < 0 ? unary_value(c.op2, o, c.cc, i)
+                                  : apply_op(c.op2, o.Vf[(int64_t)c.cc * o.ldn + i], o.Vf[(int64_t)c.cd * o.ldn + i]);
+                ff += f * f;
+                ab += a * a + b * b;
+            }
+        }
+        if (__any(bad)) ok = false;
+        if (ok && addsub) {                        // cancellation to rounding noise
+            ff = wave_sum(ff);
+            ab = wave_sum(ab);
+            if (ff <= TAU_CANCEL * TAU_CANCEL * ab) ok = false;
+        }
+        if (ok) m = wave_sum(s) / n;
+    }
+    // second pass: centred sums against the targets staged in LDS
+    double sxx = 0.0, sxy[TMAX];
+#pragma unroll
+    for (int t = 0; t < TMAX; t++) sxy[t] = 0.0;
+    for (int i0 = 0, it = 0; i0 < n; i0 += 64, it++) {
+        double(*yb)[64] = ys[it & 1];
+        for (int q = threadIdx.x; q < T * 64; q += blockDim.x) {
+            const int t = q >> 6, j = q & 63;
+            yb[t][j] = i0 + j < n ? Yc[(int64_t)t * o.ldn + i0 + j] : 0.0;
+        }
+        __syncthreads();
+        const int i = i0 + lane;
+        if (ok && i < n) {
+            const double d = cand_value(c, o, i) - m;
+            sxx += d * d;
+#pragma unroll
+            for (int t = 0; t < TMAX; t++)
+                if (t < T) sxy[t] += d * yb[t][lane];
+        }
+    }
+    __syncthreads();                               // the buffers are refilled by the next group
     double r[TMAX];
-    const bool keep = w < pvs.cap;
-    double m = 0.0, sxx = 0.0;
-    ok = ok && wave_exact_r<TMAX>(c, o, n, T, Yc, syy, r, &m, nullptr, keep ? pvs.v + w * pvs.ld : nullptr,
-                                  &sxx);
+    if (ok) {
+        sxx = wave_sum(sxx);
+        if (!isfinite(sxx)) ok = false;
+    }
+    if (ok) {
+        const double sd = sqrt(sxx / n), rms = sqrt(sxx / n + m * m);
+        if (!(sd > TAU_CONST * rms)) ok = false;
+    }
+    if (ok) {
+#pragma unroll
+        for (int t = 0; t < TMAX; t++)
+            if (t < T) r[t] = wave_sum(sxy[t]) / sqrt(sxx * syy[t]);
+    }
+    if (!has) continue;
     if (keep && lane == 0) {                              // NaN: nothing stored for this entry
         pvs.mean[w] = ok ? m : __longlong_as_double(0x7FF8000000000000LL);
         pvs.sxx[w] = ok ? sxx : __longlong_as_double(0x7FF8000000000000LL);
