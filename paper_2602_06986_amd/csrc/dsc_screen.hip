@@ -1565,7 +1565,7 @@ __device__ __forceinline__ void d_rescore(const int64_t* __restrict__ pool,
         }
         ps[w] = s;
         pex[w] = (uint8_t)ex;
-        rank[w] = 0;                                      // counted by k_rankp
+        rank[w] = 0;                                      // set by k_rk_rank
         order[w] = (int32_t)w;                            // (a valid index even before the scatter)
         const double x = sc_row[id];                      // screening-pass score
         perr[w] = s > 0.0 && x > 0.0 ? fabs(x - s) : 0.0; // its maximum is taken by k_groups
@@ -1644,23 +1644,126 @@ __device__ __forceinline__ int count_before(const SK* __restrict__ tile, int lim
     return c;
 }
 
-__device__ __forceinline__ void d_rankp(const double* __restrict__ ps, const int64_t* __restrict__ pool,
-                                        const unsigned long long* __restrict__ Pp, int64_t cap,
-                                        int32_t* __restrict__ rank) {
+// Ranks of the pool by (-score, ID) through buckets of the score: every
+// entry with a positive score goes to one of RK_NB - 1 buckets by its order
+// key relative to the smallest key (the keys are monotone in -score, and a
+// shift spreads their range over the buckets), entries scored -1 to the last
+// bucket.  A bucket's entries all precede the next bucket's, so an entry's
+// rank is the number of entries in earlier buckets (a prefix sum of the
+// bucket counts) plus the number of its bucket-mates it follows (the same
+// comparison as count_before).  The work is O(P) plus the squares of the
+// bucket sizes, and nothing depends on the order the blocks run in.
+constexpr int RK_NB = 65536;
+
+__device__ __forceinline__ uint64_t rk_key(double s) {
+    uint64_t u = (uint64_t)__double_as_longlong(s);
+    u = (u >> 63) ? ~u : (u | 0x8000000000000000ull);     // increasing with s
+    return ~u;                                             // increasing with -s
+}
+
+// Smallest key of the positive scores and the shift of their range (rkr[0]
+// holds the complement of the smallest key, rkr[1] the largest key; both
+// start at 0).
+__device__ __forceinline__ void rk_range(const unsigned long long* __restrict__ rkr, uint64_t& k0, int& sh) {
+    k0 = ~(uint64_t)rkr[0];
+    const uint64_t k1 = (uint64_t)rkr[1];
+    sh = 0;
+    if (k1 < k0) return;                                   // no positive score
+    while (((k1 - k0) >> sh) > (uint64_t)(RK_NB - 2)) sh++;
+}
+
+__device__ __forceinline__ int rk_bucket(double s, uint64_t k0, int sh) {
+    return s > 0.0 ? (int)((rk_key(s) - k0) >> sh) : RK_NB - 1;
+}
+
+__device__ __forceinline__ void d_rk_range(const double* __restrict__ ps, const unsigned long long* __restrict__ Pp,
+                                           int64_t cap, unsigned long long* __restrict__ rkr) {
     const int64_t P = min((int64_t)*Pp, cap);
-    __shared__ SK tile[RCH];
-    for (int64_t j0 = (int64_t)blockIdx.y * RCH; j0 < P; j0 += (int64_t)gridDim.y * RCH) {
+    uint64_t nk = 0, xk = 0;                               // max of ~key, max of key
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P; i += (int64_t)gridDim.x * blockDim.x) {
+        const double sv = ps[i];
+        if (!(sv > 0.0)) continue;
+        const uint64_t k = rk_key(sv);
+        nk = max(nk, ~k);
+        xk = max(xk, k);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        nk = max(nk, (uint64_t)__shfl_xor((unsigned long long)nk, o, 64));
+        xk = max(xk, (uint64_t)__shfl_xor((unsigned long long)xk, o, 64));
+    }
+    if ((threadIdx.x & 63) == 0 && (nk | xk)) {
+        atomicMax(&rkr[0], (unsigned long long)nk);
+        atomicMax(&rkr[1], (unsigned long long)xk);
+    }
+}
+
+__device__ __forceinline__ void d_rk_hist(const double* __restrict__ ps, const unsigned long long* __restrict__ Pp,
+                                          int64_t cap, const unsigned long long* __restrict__ rkr,
+                                          uint32_t* __restrict__ rkh) {
+    const int64_t P = min((int64_t)*Pp, cap);
+    uint64_t k0;
+    int sh;
+    rk_range(rkr, k0, sh);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P; i += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&rkh[rk_bucket(ps[i], k0, sh)], 1u);
+}
+
+// Exclusive prefix sum of the bucket counts, in place (one block of 1024).
+__device__ __forceinline__ void d_rk_scan(uint32_t* __restrict__ rkh) {
+    constexpr int PER = RK_NB / 1024;
+    __shared__ uint32_t part[1024];
+    const int t = threadIdx.x;
+    uint32_t sum = 0;
+    for (int q = 0; q < PER; q++) sum += rkh[t * PER + q];
+    part[t] = sum;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {                   // inclusive scan of the parts
+        const uint32_t v = t >= o ? part[t - o] : 0u;
         __syncthreads();
-        for (int q = threadIdx.x; q < RCH; q += 256)
-            tile[q] = j0 + q < P ? SK{ps[j0 + q], (long long)pool[j0 + q]} : SK{-2.0, INT64_MAX};
+        part[t] += v;
         __syncthreads();
-        const int lim = (int)min((int64_t)RCH, P - j0);
-        for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i - threadIdx.x < P;
-             i += (int64_t)gridDim.x * 256) {
-            if (i >= P) continue;
-            const int c = count_before(tile, lim, ps[i], (long long)pool[i]);
-            if (c) atomicAdd(&rank[i], c);
+    }
+    uint32_t run = part[t] - sum;
+    for (int q = 0; q < PER; q++) {
+        const uint32_t c = rkh[t * PER + q];
+        rkh[t * PER + q] = run;
+        run += c;
+    }
+}
+
+// Entries grouped by bucket: after this rkh[b] is the end of bucket b.
+__device__ __forceinline__ void d_rk_scatter(const double* __restrict__ ps, const unsigned long long* __restrict__ Pp,
+                                             int64_t cap, const unsigned long long* __restrict__ rkr,
+                                             uint32_t* __restrict__ rkh, int32_t* __restrict__ byb) {
+    const int64_t P = min((int64_t)*Pp, cap);
+    uint64_t k0;
+    int sh;
+    rk_range(rkr, k0, sh);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P; i += (int64_t)gridDim.x * blockDim.x)
+        byb[atomicAdd(&rkh[rk_bucket(ps[i], k0, sh)], 1u)] = (int32_t)i;
+}
+
+__device__ __forceinline__ void d_rk_rank(const double* __restrict__ ps, const int64_t* __restrict__ pool,
+                                          const unsigned long long* __restrict__ Pp, int64_t cap,
+                                          const unsigned long long* __restrict__ rkr,
+                                          const uint32_t* __restrict__ rkh, const int32_t* __restrict__ byb,
+                                          int32_t* __restrict__ rank) {
+    const int64_t P = min((int64_t)*Pp, cap);
+    uint64_t k0;
+    int sh;
+    rk_range(rkr, k0, sh);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P; i += (int64_t)gridDim.x * blockDim.x) {
+        const double si = ps[i];
+        const long long ii = (long long)pool[i];
+        const int b = rk_bucket(si, k0, sh);
+        const uint32_t b0 = b ? rkh[b - 1] : 0u, b1 = rkh[b];
+        int c = 0;
+        for (uint32_t q = b0; q < b1; q++) {
+            const int32_t j = byb[q];
+            const double sj = ps[j];
+            c += (int)(sj > si) | ((int)(sj == si) & (int)((long long)pool[j] < ii));
         }
+        rank[i] = (int32_t)(b0 + c);
     }
 }
 
@@ -2254,8 +2357,10 @@ struct SelArgs {
     double* ps;
     uint8_t* pex;
     unsigned long long* maxerr;
-    int32_t *order, *lo, *wc;
+    int32_t *order, *lo, *wc; // lo: pool positions grouped by rank bucket
     int32_t* rank;            // pool position -> sorted position (counted)
+    uint32_t* rkh;            // rank buckets: counts, then starts, then ends
+    unsigned long long* rkr;  // rank buckets' key range
     double* ss;               // scores in sorted order
     double* perr;             // |screening score - exact score| per pool entry
     int64_t* off;
@@ -2289,10 +2394,29 @@ __global__ __launch_bounds__(256) void k_rescore(ctab<SelArgs> A) {
 }
 
 // grid (i tiles, j chunks, lists)
-__global__ __launch_bounds__(256) void k_rankp(ctab<SelArgs> A) {
-    const SelArgs& a = tab(A, blockIdx.z);
-    DSC_GLOBAL(a.ps); DSC_GLOBAL(a.pool); DSC_GLOBAL(a.cnt); DSC_GLOBAL(a.rank); DSC_GLOBAL(a.order); DSC_GLOBAL(a.ss); DSC_GLOBAL(a.lo); DSC_GLOBAL(a.wc); DSC_GLOBAL(a.off);
-    d_rankp(a.ps, a.pool, a.cnt, a.cap, a.rank);
+__global__ __launch_bounds__(256) void k_rk_range(ctab<SelArgs> A) {
+    const SelArgs& a = tab(A, blockIdx.y);
+    d_rk_range(a.ps, a.cnt, a.cap, a.rkr);
+}
+
+__global__ __launch_bounds__(256) void k_rk_hist(ctab<SelArgs> A) {
+    const SelArgs& a = tab(A, blockIdx.y);
+    d_rk_hist(a.ps, a.cnt, a.cap, a.rkr, a.rkh);
+}
+
+__global__ __launch_bounds__(1024) void k_rk_scan(ctab<SelArgs> A) {
+    const SelArgs& a = tab(A, blockIdx.x);
+    d_rk_scan(a.rkh);
+}
+
+__global__ __launch_bounds__(256) void k_rk_scatter(ctab<SelArgs> A) {
+    const SelArgs& a = tab(A, blockIdx.y);
+    d_rk_scatter(a.ps, a.cnt, a.cap, a.rkr, a.rkh, a.lo);
+}
+
+__global__ __launch_bounds__(256) void k_rk_rank(ctab<SelArgs> A) {
+    const SelArgs& a = tab(A, blockIdx.y);
+    d_rk_rank(a.ps, a.pool, a.cnt, a.cap, a.rkr, a.rkh, a.lo, a.rank);
 }
 
 __global__ __launch_bounds__(256) void k_scatter(ctab<SelArgs> A) {
@@ -3162,6 +3286,7 @@ static char* sel_layout(discover_ctx* ctx, int k, const std::vector<ListState>& 
         v.push_back(ar.add(pvc * (size_t)L.n * 8)); // stored pool values
         v.push_back(ar.add(pvc * 8));              // their means
         v.push_back(ar.add(pvc * 8));              // their centred sums of squares
+        v.push_back(ar.add(RK_NB * 4 + 64));       // rank buckets and their key range
     }
     return (char*)ctx->raw("sel_arena" + ctx->tag, ar.total);
 }
@@ -3252,6 +3377,7 @@ static void select_round(discover_ctx* ctx, const discover_problem* probs,
         char* misc = at();
         uint32_t* hist = (uint32_t*)at();
         a.pvs.v = (double*)at(); a.pvs.mean = (double*)at(); a.pvs.sxx = (double*)at();
+        a.rkh = (uint32_t*)at(); a.rkr = (unsigned long long*)(a.rkh + RK_NB);
         a.pvs.ld = L.n; a.pvs.cap = pool_vals_cap(L.cap, L.n);
         a.cnt = (unsigned long long*)misc;
         a.maxerr = (unsigned long long*)(misc + 8);
@@ -3275,6 +3401,7 @@ static void select_round(discover_ctx* ctx, const discover_problem* probs,
         ra[q] = RadixArgs{a.sc, P.N, L.K, hist, sel, stv, nullptr};
         fills.push_back(fill_seg(misc, 64, 0u));            // pool count, maximum error, st, sel, clusters, prefix
         fills.push_back(fill_seg(hist, 8192 * 4, 0u));
+        fills.push_back(fill_seg(a.rkh, RK_NB * 4 + 64, 0u));
         Nmax = std::max(Nmax, P.N);
         capmax = std::max(capmax, L.cap);
         Kmax = std::max(Kmax, L.K);
@@ -3304,10 +3431,13 @@ static void select_round(discover_ctx* ctx, const discover_problem* probs,
     }
     {
         KTimer kt(ctx, st, "sort_dedup");
-        // ranks over tiles of the expected pool size (grid-strided beyond it)
-        const unsigned ri = (unsigned)std::max<int64_t>(1, std::min<int64_t>(64, cdiv(Kmax + 256, 256)));
-        const unsigned rj = (unsigned)std::max<int64_t>(1, std::min<int64_t>(64, cdiv(Kmax + 256, RCH)));
-        k_rankp<<<dim3(ri, rj, nl), 256, 0, st>>>(dsa);
+        // ranks through score buckets (grid-strided over the pool)
+        const unsigned rb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(1024, cdiv(capmax, 256)));
+        k_rk_range<<<dim3(rb, nl), 256, 0, st>>>(dsa);
+        k_rk_hist<<<dim3(rb, nl), 256, 0, st>>>(dsa);
+        k_rk_scan<<<nl, 1024, 0, st>>>(dsa);
+        k_rk_scatter<<<dim3(rb, nl), 256, 0, st>>>(dsa);
+        k_rk_rank<<<dim3(rb, nl), 256, 0, st>>>(dsa);
         k_scatter<<<dim3((unsigned)std::min<int64_t>(1024, cdiv(capmax, 256)), nl), 256, 0, st>>>(dsa);
         k_clusters<<<dim3((unsigned)std::min<int64_t>(1024, cdiv(capmax, 256)), nl), 256, 0, st>>>(dsa);
         check_launch("k_sort");
@@ -3475,6 +3605,7 @@ static void generate_screen_once(discover_ctx* ctx, const discover_problem* prob
         for (size_t q = 0; q < act.size(); q++) {
             fills.push_back(fill_seg(base + o[q][SEL_MISC], 64, 0u));   // pool count, maximum error, st, sel, clusters, prefix
             fills.push_back(fill_seg(base + o[q][SEL_HIST], 8192 * 4, 0u));
+            fills.push_back(fill_seg(base + o[q].back(), RK_NB * 4 + 64, 0u));   // rank buckets
         }
     };
     screen_all(ctx, probs, nb, prm, PS, st, first_round);
