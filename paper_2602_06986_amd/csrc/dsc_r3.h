@@ -61,8 +61,13 @@ inline size_t r3_as_offset(const R3Plan& p, int TP, int n) {
     const size_t lp = (size_t)p.n_ctiles * r3_chunks(n) * 512 * (4 + TP * 2);
     return (std::max(f64, lp) + 255) & ~(size_t)255;
 }
-inline size_t r3_bmat_bytes(const R3Plan& p, int TP, int n) {
+// The add/sub tiles' operands end with the targets in the same lane order
+// (one 16-column block: column t = target t), at r3_asy_offset bytes.
+inline size_t r3_asy_offset(const R3Plan& p, int TP, int n) {
     return r3_as_offset(p, TP, n) + (size_t)p.n_as_ctiles * (TP + 2) * r3_quads(n) * 64 * 8;
+}
+inline size_t r3_bmat_bytes(const R3Plan& p, int TP, int n) {
+    return r3_asy_offset(p, TP, n) + (size_t)r3_quads(n) * 64 * 8;
 }
 inline size_t r3_pstat_bytes(const R3Plan& p, int TP) {
     return (size_t)std::max(p.pe, 1) * (2 + TP + 2) * 8;

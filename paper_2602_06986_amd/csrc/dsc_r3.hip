@@ -206,6 +206,18 @@ __global__ __launch_bounds__(256) void k_r3_bmat(int n, int64_t ldn, int TP, int
     }
 }
 
+// The targets in the B lane order: yb[q 64 + 4 j + e] = y_j at sample 4q + e
+// (0 for j >= TP and samples >= n).
+__global__ __launch_bounds__(256) void k_r3_ybmat(int n, int64_t ldn, int TP, int NQ,
+                                                  const double* __restrict__ Yn, double* __restrict__ yb) {
+    const int64_t total = (int64_t)NQ * 64;
+    for (int64_t f = (int64_t)blockIdx.x * 256 + threadIdx.x; f < total; f += (int64_t)gridDim.x * 256) {
+        const int e = (int)(f & 3), j = (int)((f >> 2) & 15);
+        const int s = 4 * (int)(f >> 6) + e;
+        yb[f] = j < TP && s < n ? Yn[(int64_t)j * ldn + s] : 0.0;
+    }
+}
+
 // ------------------------------------------------------------ MFMA screen
 struct R3mArgs {
     const int2* grec;
@@ -217,6 +229,7 @@ struct R3mArgs {
     int n_gct, n_gblk, NQ, n, T, mode;
     int64_t ldn;
     const double* bmat;
+    const double* ybmat;      // add / sub: the targets (k_r3_ybmat)
     const double *Vf, *Rf;
     const double* pstat;
     int pe;
@@ -291,6 +304,32 @@ __global__ __launch_bounds__(256) void k_r3_mm(R3mArgs g) {
 
     const double* bp = g.bmat + (int64_t)ct * TK * g.NQ * 64 + lane * 4;
     const int nm = g.NQ >> 2;
+    if constexpr (AS) {
+        // add / sub need per row only sum g y_t, sum g, sum g^2 and per pair
+        // sum x g: three product streams, g against [x | 1] (acc[0][TP]),
+        // against the targets (acc[0][0], column t = target t) and g^2
+        // against [x^2 | 1] (acc[0][TP + 1], its column of ones)
+        const double* yp = g.ybmat + lane * 4;
+        for (int m = 0; m < nm; m++) {
+            const int s = 16 * m + 4 * kq;
+            r3_v4d v = r3_combine(oo[0], *(const r3_v4d*)(p1[0] + s), *(const r3_v4d*)(p2[0] + s));
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const bool in = rok[0] && s + e < g.n;
+                v[e] = in ? v[e] : 0.0;
+            }
+            const r3_v4d v2 = v * v;
+            const r3_v4d bx = *(const r3_v4d*)(bp + ((int64_t)TP * g.NQ + 4 * m) * 64);
+            const r3_v4d bq = *(const r3_v4d*)(bp + ((int64_t)(TP + 1) * g.NQ + 4 * m) * 64);
+            const r3_v4d by = *(const r3_v4d*)(yp + (int64_t)(4 * m) * 64);
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[e], by[e], acc[0][0], 0, 0, 0);
+                acc[0][TP] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[e], bx[e], acc[0][TP], 0, 0, 0);
+                acc[0][TP + 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(v2[e], bq[e], acc[0][TP + 1], 0, 0, 0);
+            }
+        }
+    } else {
     for (int m = 0; m < nm; m++) {
         const int s = 16 * m + 4 * kq;
         r3_v4d A[GT], A2[GT];
@@ -324,6 +363,7 @@ __global__ __launch_bounds__(256) void k_r3_mm(R3mArgs g) {
             }
         }
     }
+    }
     // row ranges over the four sample groups of each row
 #pragma unroll
     for (int u = 0; u < GT; u++) {
@@ -351,9 +391,11 @@ __global__ __launch_bounds__(256) void k_r3_mm(R3mArgs g) {
 #pragma unroll
         for (int r = 0; r < 4; r++) {
             const int i = kq + 4 * r;
-            double gs[TK];
+            double gs[TK];                             // sum g y_t, sum g, sum g^2 of row i
 #pragma unroll
-            for (int t = 0; t < TK; t++) gs[t] = __shfl(acc[0][t][r], src, 64);
+            for (int t = 0; t < TP; t++) gs[t] = __shfl(acc[0][0][r], (lane & 48) | t, 64);
+            gs[TP] = __shfl(acc[0][TP][r], src, 64);
+            gs[TP + 1] = __shfl(acc[0][TP + 1][r], src, 64);
             const bool ok = __shfl((int)rok[0], i, 64) != 0 && colok;
             const int64_t gj = __shfl(j2[0], i, 64);
             if (!ok) continue;
@@ -1090,9 +1132,13 @@ void launch_r3(discover_ctx* ctx, const R3Launch& a, hipStream_t st) {
         k_r3_bmat<<<(unsigned)std::min<int64_t>(cdiv(tot, 256), 16384), 256, 0, st>>>(
             a.n, a.ldn, a.TP, NQ, P.n_as_ctiles, P.as_coldesc, a.Vf, a.Rf, a.Yn, bm);
         check_launch("k_r3_bmat");
+        double* yb = (double*)((char*)a.bmat + r3_asy_offset(P, a.TP, a.n));
+        k_r3_ybmat<<<(unsigned)std::min<int64_t>(cdiv((int64_t)NQ * 64, 256), 4096), 256, 0, st>>>(
+            a.n, a.ldn, a.TP, NQ, a.Yn, yb);
+        check_launch("k_r3_ybmat");
         R3mArgs m{};
         m.grec = P.as_grec; m.n_grec = P.n_as_grec; m.work = P.as_work; m.n_work = P.n_as_work;
-        m.pconst = pc; m.coldesc = P.as_coldesc; m.n_gct = 0;
+        m.pconst = pc; m.coldesc = P.as_coldesc; m.n_gct = 0; m.ybmat = yb;
         m.NQ = NQ; m.n = a.n; m.T = a.T; m.mode = a.mode; m.ldn = a.ldn; m.bmat = bm;
         m.Vf = a.Vf; m.Rf = a.Rf; m.pstat = a.pstat; m.pe = P.pe; m.ops = P.ops;
         m.valid = a.valid; m.mat_raw = a.mat_raw; m.r2v = a.r2v; m.ysum = a.ysum; m.sd = a.sd;
