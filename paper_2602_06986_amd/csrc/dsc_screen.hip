@@ -2777,10 +2777,11 @@ struct ListState {
 };
 
 // Pool entries whose values the rescoring keeps for the duplicate pairs:
-// up to 1 GB of values per list (every entry of a pool of n = 2000 samples
-// up to 65,536 entries).
+// up to 4 GB of values per list (every entry of a pool of n = 2000 samples
+// up to 268,435 entries; the pool's order is not the score order, so the
+// entries the groups compare are spread over the whole pool).
 static int64_t pool_vals_cap(int64_t cap, int n) {
-    return std::min<int64_t>(cap, ((int64_t)1 << 30) / (8 * (int64_t)std::max(n, 1)));
+    return std::min<int64_t>(cap, ((int64_t)1 << 32) / (8 * (int64_t)std::max(n, 1)));
 }
 
 // Allocate every problem's working memory for one call.
