@@ -53,11 +53,11 @@ SWEEP3_COUNTERS = {
 R3_COUNTERS = {
     # the precision form: totals of the k_r3_lp kernels of one dimension
     "k_r3_lp": {"source": "paper_2602_06986_amd/csrc/dsc_r3.hip",
-                "sha256": "de9a0192ea6f3e4a00da4d60ce7d8f6af1a8761c666965edcd616289c4a7d24c",
-                "fetch_kib": 19366297.4, "fetch_scale": 1.99992, "write_kib": 1505145.6, "write_scale": 1.0},
+                "sha256": "9446a60d999383dafd19f8d9adb49519ea2a38c0514c1d937dc5de20600d6fb8",
+                "fetch_kib": 20431963.8, "fetch_scale": 1.99992, "write_kib": 1481079.6, "write_scale": 1.0},
     "k_r3_mm": {"source": "paper_2602_06986_amd/csrc/dsc_r3.hip",
-                "sha256": "de9a0192ea6f3e4a00da4d60ce7d8f6af1a8761c666965edcd616289c4a7d24c",
-                "fetch_kib": 23409671.7, "fetch_scale": 1.99992, "write_kib": 1300214.4, "write_scale": 1.0},
+                "sha256": "9446a60d999383dafd19f8d9adb49519ea2a38c0514c1d937dc5de20600d6fb8",
+                "fetch_kib": 23578555.8, "fetch_scale": 1.99992, "write_kib": 1300224.6, "write_scale": 1.0},
 }
 
 
