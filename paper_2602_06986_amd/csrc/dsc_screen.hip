@@ -1522,7 +1522,9 @@ __device__ __forceinline__ void d_rescore(const int64_t* __restrict__ pool,
         __syncthreads();
         const int i = i0 + lane;
         if (ok && i < n) {
-            const double d = cand_value(c, o, i) - m;
+            // the first pass's values: stored (read back by the lane that
+            // wrote them) or evaluated again
+            const double d = (vals ? vals[i] : cand_value(c, o, i)) - m;
             sxx += d * d;
 #pragma unroll
             for (int t = 0; t < TMAX; t++)
