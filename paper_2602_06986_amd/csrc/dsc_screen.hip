@@ -1567,7 +1567,7 @@ __device__ __forceinline__ void d_rescore(const int64_t* __restrict__ pool,
         }
         ps[w] = s;
         pex[w] = (uint8_t)ex;
-        rank[w] = 0;                                      // set by k_rk_rank
+        rank[w] = 0;                                      // counted by k_rankp or set by k_rk_rank
         order[w] = (int32_t)w;                            // (a valid index even before the scatter)
         const double x = sc_row[id];                      // screening-pass score
         perr[w] = s > 0.0 && x > 0.0 ? fabs(x - s) : 0.0; // its maximum is taken by k_groups
@@ -1646,7 +1646,30 @@ __device__ __forceinline__ int count_before(const SK* __restrict__ tile, int lim
     return c;
 }
 
-// Ranks of the pool by (-score, ID) through buckets of the score: every
+// Small pools: the rank of entry i is the number of entries j before it,
+// counted over tiles of 256 entries i and chunks of RCH entries j staged in
+// LDS (grid-strided over both) with integer atomics.
+__device__ __forceinline__ void d_rankp(const double* __restrict__ ps, const int64_t* __restrict__ pool,
+                                        const unsigned long long* __restrict__ Pp, int64_t cap,
+                                        int32_t* __restrict__ rank) {
+    const int64_t P = min((int64_t)*Pp, cap);
+    __shared__ SK tile[RCH];
+    for (int64_t j0 = (int64_t)blockIdx.y * RCH; j0 < P; j0 += (int64_t)gridDim.y * RCH) {
+        __syncthreads();
+        for (int q = threadIdx.x; q < RCH; q += 256)
+            tile[q] = j0 + q < P ? SK{ps[j0 + q], (long long)pool[j0 + q]} : SK{-2.0, INT64_MAX};
+        __syncthreads();
+        const int lim = (int)min((int64_t)RCH, P - j0);
+        for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i - threadIdx.x < P;
+             i += (int64_t)gridDim.x * 256) {
+            if (i >= P) continue;
+            const int c = count_before(tile, lim, ps[i], (long long)pool[i]);
+            if (c) atomicAdd(&rank[i], c);
+        }
+    }
+}
+
+// Large pools: ranks of the pool by (-score, ID) through buckets of the score: every
 // entry with a positive score goes to one of RK_NB - 1 buckets by its order
 // key relative to the smallest key (the keys are monotone in -score, and a
 // shift spreads their range over the buckets), entries scored -1 to the last
@@ -1656,6 +1679,7 @@ __device__ __forceinline__ int count_before(const SK* __restrict__ tile, int lim
 // comparison as count_before).  The work is O(P) plus the squares of the
 // bucket sizes, and nothing depends on the order the blocks run in.
 constexpr int RK_NB = 65536;
+constexpr int64_t RANK_PAIRS_MAX = 16384;   // pool capacity up to which all pairs are counted
 
 __device__ __forceinline__ uint64_t rk_key(double s) {
     uint64_t u = (uint64_t)__double_as_longlong(s);
@@ -2396,6 +2420,11 @@ __global__ __launch_bounds__(256) void k_rescore(ctab<SelArgs> A) {
 }
 
 // grid (i tiles, j chunks, lists)
+__global__ __launch_bounds__(256) void k_rankp(ctab<SelArgs> A) {
+    const SelArgs& a = tab(A, blockIdx.z);
+    d_rankp(a.ps, a.pool, a.cnt, a.cap, a.rank);
+}
+
 __global__ __launch_bounds__(256) void k_rk_range(ctab<SelArgs> A) {
     const SelArgs& a = tab(A, blockIdx.y);
     d_rk_range(a.ps, a.cnt, a.cap, a.rkr);
@@ -3434,13 +3463,21 @@ static void select_round(discover_ctx* ctx, const discover_problem* probs,
     }
     {
         KTimer kt(ctx, st, "sort_dedup");
-        // ranks through score buckets (grid-strided over the pool)
-        const unsigned rb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(1024, cdiv(capmax, 256)));
-        k_rk_range<<<dim3(rb, nl), 256, 0, st>>>(dsa);
-        k_rk_hist<<<dim3(rb, nl), 256, 0, st>>>(dsa);
-        k_rk_scan<<<nl, 1024, 0, st>>>(dsa);
-        k_rk_scatter<<<dim3(rb, nl), 256, 0, st>>>(dsa);
-        k_rk_rank<<<dim3(rb, nl), 256, 0, st>>>(dsa);
+        if (capmax <= RANK_PAIRS_MAX) {
+            // ranks by counting over all pairs (tiles of the expected pool size,
+            // grid-strided beyond it): one launch, for pools of a few thousand
+            const unsigned ri = (unsigned)std::max<int64_t>(1, std::min<int64_t>(64, cdiv(Kmax + 256, 256)));
+            const unsigned rj = (unsigned)std::max<int64_t>(1, std::min<int64_t>(64, cdiv(Kmax + 256, RCH)));
+            k_rankp<<<dim3(ri, rj, nl), 256, 0, st>>>(dsa);
+        } else {
+            // ranks through score buckets (grid-strided over the pool)
+            const unsigned rb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(1024, cdiv(capmax, 256)));
+            k_rk_range<<<dim3(rb, nl), 256, 0, st>>>(dsa);
+            k_rk_hist<<<dim3(rb, nl), 256, 0, st>>>(dsa);
+            k_rk_scan<<<nl, 1024, 0, st>>>(dsa);
+            k_rk_scatter<<<dim3(rb, nl), 256, 0, st>>>(dsa);
+            k_rk_rank<<<dim3(rb, nl), 256, 0, st>>>(dsa);
+        }
         k_scatter<<<dim3((unsigned)std::min<int64_t>(1024, cdiv(capmax, 256)), nl), 256, 0, st>>>(dsa);
         k_clusters<<<dim3((unsigned)std::min<int64_t>(1024, cdiv(capmax, 256)), nl), 256, 0, st>>>(dsa);
         check_launch("k_sort");
