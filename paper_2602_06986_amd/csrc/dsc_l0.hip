@@ -182,9 +182,15 @@ struct SweepArgs {
     unsigned long long* lcnt;
 };
 
+// 1/x by the hardware reciprocal and one Newton step.  The residual e = 1 -
+// x r (one FMA, exact to its rounding) is r's relative error, and the
+// Newton step leaves about e^2: when |e| exceeds 2^-20 (never seen on
+// gfx950) the correctly rounded quotient is taken instead, so the result
+// is within 2^-40 of 1/x whatever the hardware reciprocal's accuracy.
 __device__ __forceinline__ double fast_rcp(double x) {
     double r = __builtin_amdgcn_rcp(x);
     const double e = fma(-x, r, 1.0);
+    if (!(fabs(e) <= 9.5367431640625e-7)) return 1.0 / x;
     return fma(r, e, r);
 }
 
@@ -341,12 +347,17 @@ __device__ __forceinline__ double sw3_keep(double low, double x, bool ok) {
 }
 
 // The sweep's own value, -q~ with q~ = e^2 * rcp(den) + Q_ab, where rcp is
-// the bare hardware reciprocal (relative error below 2^-24 measured on
-// gfx950; SW3_RCP_DELTA allows 2^-21 of the explained fraction).  w is the
+// the bare hardware reciprocal; SW3_RCP_DELTA allows 2^-21 of the explained
+// fraction for its error.  The residual 1 - den rcp (one FMA, exact to its
+// rounding) is that error: a reciprocal further than 2^-22 off (never seen
+// on gfx950, whose error stays below 2^-24.3) is replaced by the correctly
+// rounded quotient, so the allowance holds by construction.  w is the
 // table's Q_ab - th; adding th back costs one rounding of Q_ab, far inside
 // the band's allowances.
 __device__ __forceinline__ double sw3_negq(double ee2, double den, double w, double th) {
-    return fma(-ee2, __builtin_amdgcn_rcp(den), -(w + th));
+    double r = __builtin_amdgcn_rcp(den);
+    if (!(fabs(fma(-den, r, 1.0)) <= 2.384185791015625e-7)) r = 1.0 / den;
+    return fma(-ee2, r, -(w + th));
 }
 
 // One row b of a wave, from its loaded G entry C and factor entries E.  In
