@@ -20,7 +20,8 @@
 namespace dsc {
 
 struct R3Plan {
-    // every unit-legal rung-2 feature, in ID order: x = k (compact operand,
+    // every unit-legal rung-2 feature, per operator (binary ones in windows
+    // of 64 x 64 operands, for L2 reuse): x = k (compact operand,
     // -1 for a unary operator), y = l | op2 << 28
     int2* grec = nullptr;
     int64_t n_grec = 0;

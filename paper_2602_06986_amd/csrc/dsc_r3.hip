@@ -42,6 +42,16 @@ typedef double r3_v4d __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ int r3_wave() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
+// Workgroups are dealt to the 8 XCDs in turn (block b to XCD b % 8); this
+// numbering gives each XCD a contiguous range of the grid's logical blocks,
+// so that the row tiles one XCD works on at a time are neighbours in the
+// record order and share their operand rows in that XCD's L2.
+__device__ __forceinline__ int r3_xcd_block() {
+    const int nb = (int)gridDim.x, b = (int)blockIdx.x;
+    const int per = nb >> 3, rem = nb & 7, x = b & 7, pos = b >> 3;
+    return x < rem ? x * (per + 1) + pos : rem * (per + 1) + (x - rem) * per + pos;
+}
+
 // Slot of each active lane in a list (lane order), one atomic per wave.
 __device__ __forceinline__ unsigned long long r3_slot(unsigned long long* ctr) {
     const uint64_t m = __builtin_amdgcn_ballot_w64(true);
@@ -262,8 +272,9 @@ __global__ __launch_bounds__(256) void k_r3_mm(R3mArgs g) {
         tile0 = wk.x;
         ct = wk.y;
     } else {
-        ct = blockIdx.x / g.n_gblk;                    // column tile (slowest: its operands stay in L2)
-        const int gb = blockIdx.x - ct * g.n_gblk;
+        const int lb = r3_xcd_block();
+        ct = lb / g.n_gblk;                            // column tile (slowest: its operands stay in L2)
+        const int gb = lb - ct * g.n_gblk;
         tile0 = ((int64_t)gb * 4 + r3_wave()) * GT;
         if (tile0 * 16 >= g.n_grec) return;
     }
@@ -617,9 +628,10 @@ __global__ __launch_bounds__(256, (TP * CT <= 16 ? 2 : 1)) void k_r3_lp(R3lpArgs
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int r16 = lane & 15, kq = lane >> 4;
-    const int cb = blockIdx.x / g.n_gblk;
+    const int lb = r3_xcd_block();
+    const int cb = lb / g.n_gblk;
     const int ctb = a.ct0 + cb * CT;                     // first column tile of the block
-    const int64_t tile0 = (int64_t)(blockIdx.x - cb * g.n_gblk) * 4 + r3_wave();
+    const int64_t tile0 = (int64_t)(lb - cb * g.n_gblk) * 4 + r3_wave();
     // a wave without a row tile still stages its share and meets every barrier
     const bool active = tile0 * 16 < g.n_grec;
     constexpr bool hk = HK;
@@ -962,7 +974,8 @@ std::shared_ptr<R3Plan> build_r3_plan(const Space& sp, uint32_t r3_ops) {
     DSC_REQUIRE(c1 < (1 << 28), "rung-1 operand count too large");
     const int pool2 = d.pool[2];
     const bool addsub = (r3_ops & 3u) != 0;
-    // every unit-legal rung-2 feature, in ID order, with its unit vector
+    // every unit-legal rung-2 feature with its unit vector (unary operators
+    // in ID order, binary ones in windows of operands, below)
     std::vector<int2> rec;
     std::vector<int32_t> gunit;
     std::vector<int32_t> u2(Bq, 0);
@@ -984,14 +997,21 @@ std::shared_ptr<R3Plan> build_r3_plan(const Space& sp, uint32_t r3_ops) {
             if (unit_rule(o, B, &sp.mat_unit[(size_t)l * Bq], nullptr, u2.data())) push(-1, l, o);
         pad16(o);
     }
+    // binary records in windows of R3_SW operands l by R3_SW operands k: the
+    // tiles of a window need 2 R3_SW operand rows, which stay in L2 while
+    // its tiles run (the kernels keep neighbouring blocks on one XCD)
+    constexpr int32_t R3_SW = 64;
+    const int32_t kend = pool2 == 1 ? c1 : sp.rung_start[pool2 + 1];
     for (int o = OP_ADD; o <= OP_RDIV; o++) {
         if (d.block[2][o] < 0) continue;
-        for (int32_t l = c0; l < c1; l++) {
-            const int32_t kmax = pool2 == 1 ? l : sp.rung_start[pool2 + 1];
-            for (int32_t k = 0; k < kmax; k++)
-                if (unit_rule(o, B, &sp.mat_unit[(size_t)k * Bq], &sp.mat_unit[(size_t)l * Bq], u2.data()))
-                    push(k, l, o);
-        }
+        for (int32_t l0 = c0; l0 < c1; l0 += R3_SW)
+            for (int32_t k0 = 0; k0 < kend; k0 += R3_SW)
+                for (int32_t l = l0; l < std::min(l0 + R3_SW, c1); l++) {
+                    const int32_t kmax = std::min(pool2 == 1 ? l : sp.rung_start[pool2 + 1], k0 + R3_SW);
+                    for (int32_t k = k0; k < kmax; k++)
+                        if (unit_rule(o, B, &sp.mat_unit[(size_t)k * Bq], &sp.mat_unit[(size_t)l * Bq], u2.data()))
+                            push(k, l, o);
+                }
         pad16(o);
     }
     P->n_grec = (int64_t)rec.size();
