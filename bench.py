@@ -40,9 +40,9 @@ L0_FLOP_PER_SUBSET = 12
 # plain 1 GiB device copy.  Valid only for the kernel source they were taken on.
 SWEEP3_COUNTERS = {
     "source": "paper_2602_06986_amd/csrc/dsc_l0.hip",
-    "sha256": "dc7e031dddfaedd56ca3d2e16d20c1c8a8db703a0b5c46309016cea6b90e3201",
-    "fetch_kib": 76979.4, "fetch_scale": 1.99991,
-    "write_kib": 15203.6, "write_scale": 1.0,
+    "sha256": "2463cfec93b221d5a479c2e98b9d74609a59c7678e14f519db96e8cca0f5d4fc",
+    "fetch_kib": 76895.2, "fetch_scale": 1.99991,
+    "write_kib": 15214.6, "write_scale": 1.0,
 }
 
 
@@ -53,11 +53,11 @@ SWEEP3_COUNTERS = {
 R3_COUNTERS = {
     # the precision form: totals of the k_r3_lp kernels of one dimension
     "k_r3_lp": {"source": "paper_2602_06986_amd/csrc/dsc_r3.hip",
-                "sha256": "9446a60d999383dafd19f8d9adb49519ea2a38c0514c1d937dc5de20600d6fb8",
-                "fetch_kib": 20431963.8, "fetch_scale": 1.99992, "write_kib": 1481079.6, "write_scale": 1.0},
+                "sha256": "81ba33d12238a00f2f4a824bf5b21a4e4d9f95730669143c6fba0b5f4321430d",
+                "fetch_kib": 1474688.9, "fetch_scale": 1.99992, "write_kib": 1215267.7, "write_scale": 1.0},
     "k_r3_mm": {"source": "paper_2602_06986_amd/csrc/dsc_r3.hip",
-                "sha256": "9446a60d999383dafd19f8d9adb49519ea2a38c0514c1d937dc5de20600d6fb8",
-                "fetch_kib": 23578555.8, "fetch_scale": 1.99992, "write_kib": 1300224.6, "write_scale": 1.0},
+                "sha256": "81ba33d12238a00f2f4a824bf5b21a4e4d9f95730669143c6fba0b5f4321430d",
+                "fetch_kib": 6180863.9, "fetch_scale": 1.99992, "write_kib": 1299419.7, "write_scale": 1.0},
 }
 
 
