@@ -2411,10 +2411,13 @@ __global__ __launch_bounds__(256) void k_compact(ctab<SelArgs> A) {
     d_compact(a.sc, a.N, a.hist, a.sel, a.st, a.margin, a.cap, a.pool, a.cnt, a.K);
 }
 
+// TM: the most targets of any list of the launch (1, 8 or 16 registers of
+// sums per lane).
+template <int TM>
 __global__ __launch_bounds__(256) void k_rescore(ctab<SelArgs> A) {
     const SelArgs& a = tab(A, blockIdx.y);
     DSC_GLOBAL(a.sc); DSC_GLOBAL(a.sel); DSC_GLOBAL(a.st); DSC_GLOBAL(a.pool); DSC_GLOBAL(a.cnt); DSC_GLOBAL(a.ev.raw2c); DSC_GLOBAL(a.ev.valid); DSC_GLOBAL(a.o.Vf); DSC_GLOBAL(a.o.Rf); DSC_GLOBAL(a.Yc); DSC_GLOBAL(a.syy); DSC_GLOBAL(a.ps); DSC_GLOBAL(a.pex); DSC_GLOBAL(a.maxerr); DSC_GLOBAL(a.order); DSC_GLOBAL(a.lo); DSC_GLOBAL(a.wc); DSC_GLOBAL(a.off); DSC_GLOBAL(a.flag); DSC_GLOBAL(a.parent); DSC_GLOBAL(a.blk); DSC_GLOBAL(a.repid); DSC_GLOBAL(a.reppos); DSC_GLOBAL(a.headpos); DSC_GLOBAL(a.out_ids); DSC_GLOBAL(a.out_sc); DSC_GLOBAL(a.res);
-    d_rescore<DISCOVER_MAX_TARGETS>(a.pool, a.cnt, a.cap, a.ev, a.o, a.n, a.T, a.mode, a.t, a.Yc, a.syy,
+    d_rescore<TM>(a.pool, a.cnt, a.cap, a.ev, a.o, a.n, a.T, a.mode, a.t, a.Yc, a.syy,
                                     a.excl, a.n_excl, a.ps, a.pex, a.sc, a.perr, a.rank, a.order, a.pvs,
                                     a.rules);
 }
@@ -3450,15 +3453,12 @@ static void select_round(discover_ctx* ctx, const discover_problem* probs,
     check_launch("k_compact");
     {
         KTimer kt(ctx, st, "rescore");
-#ifndef RESCORE_GRID
-#define RESCORE_GRID 0
-#endif
-#if RESCORE_GRID == 0
-        k_rescore<<<dim3((unsigned)std::min<int64_t>(std::max(64, 2048 / nl), cdiv(capmax, 4)), nl), 256, 0, st>>>(dsa);
-#else
-        // one wave per expected pool entry (grid-strided beyond)
-        k_rescore<<<dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(Kmax + 64, 4), cdiv(capmax, 4))), nl), 256, 0, st>>>(dsa);
-#endif
+        int Tm = 1;
+        for (const SelArgs& x : sa) Tm = std::max(Tm, x.T);
+        const dim3 rg((unsigned)std::min<int64_t>(std::max(64, 2048 / nl), cdiv(capmax, 4)), nl);
+        if (Tm <= 1) k_rescore<1><<<rg, 256, 0, st>>>(dsa);
+        else if (Tm <= 8) k_rescore<8><<<rg, 256, 0, st>>>(dsa);
+        else k_rescore<DISCOVER_MAX_TARGETS><<<rg, 256, 0, st>>>(dsa);
         check_launch("k_rescore");
     }
     {
