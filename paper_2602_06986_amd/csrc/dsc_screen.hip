@@ -1669,15 +1669,17 @@ __device__ __forceinline__ void d_rankp(const double* __restrict__ ps, const int
     }
 }
 
-// Large pools: ranks of the pool by (-score, ID) through buckets of the score: every
-// entry with a positive score goes to one of RK_NB - 1 buckets by its order
-// key relative to the smallest key (the keys are monotone in -score, and a
-// shift spreads their range over the buckets), entries scored -1 to the last
-// bucket.  A bucket's entries all precede the next bucket's, so an entry's
-// rank is the number of entries in earlier buckets (a prefix sum of the
-// bucket counts) plus the number of its bucket-mates it follows (the same
-// comparison as count_before).  The work is O(P) plus the squares of the
-// bucket sizes, and nothing depends on the order the blocks run in.
+// Large pools: ranks of the pool by (-score, ID) through buckets: an entry
+// with a positive score goes to one of the first RK_NB / 2 buckets by its
+// order key relative to the smallest key (the keys are monotone in -score,
+// and a shift spreads their range over the buckets), an entry scored -1 to
+// one of the last RK_NB / 2 by its ID relative to the smallest such ID (the
+// order among equal scores).  A bucket's entries all precede the next
+// bucket's, so an entry's rank is the number of entries in earlier buckets
+// (a prefix sum of the bucket counts) plus the number of its bucket-mates
+// it follows (the same comparison as count_before).  The work is O(P) plus
+// the squares of the bucket sizes, and nothing depends on the order the
+// blocks run in.
 constexpr int RK_NB = 65536;
 constexpr int64_t RANK_PAIRS_MAX = 16384;   // pool capacity up to which all pairs are counted
 
@@ -1687,51 +1689,67 @@ __device__ __forceinline__ uint64_t rk_key(double s) {
     return ~u;                                             // increasing with -s
 }
 
-// Smallest key of the positive scores and the shift of their range (rkr[0]
-// holds the complement of the smallest key, rkr[1] the largest key; both
-// start at 0).
-__device__ __forceinline__ void rk_range(const unsigned long long* __restrict__ rkr, uint64_t& k0, int& sh) {
-    k0 = ~(uint64_t)rkr[0];
-    const uint64_t k1 = (uint64_t)rkr[1];
-    sh = 0;
-    if (k1 < k0) return;                                   // no positive score
-    while (((k1 - k0) >> sh) > (uint64_t)(RK_NB - 2)) sh++;
+// The buckets' origins and shifts: rkr[0] / rkr[1] hold the complement of
+// the smallest and the largest key of the positive scores, rkr[2] / rkr[3]
+// the complement of the smallest and the largest ID of the entries scored
+// -1 (all start at 0).
+struct RkMap {
+    uint64_t k0, i0;
+    int sh, shi;
+};
+
+__device__ __forceinline__ int rk_shift(uint64_t lo, uint64_t hi) {
+    int sh = 0;
+    if (hi < lo) return 0;                                 // none
+    while (((hi - lo) >> sh) > (uint64_t)(RK_NB / 2 - 1)) sh++;
+    return sh;
 }
 
-__device__ __forceinline__ int rk_bucket(double s, uint64_t k0, int sh) {
-    return s > 0.0 ? (int)((rk_key(s) - k0) >> sh) : RK_NB - 1;
+__device__ __forceinline__ RkMap rk_map(const unsigned long long* __restrict__ rkr) {
+    RkMap m;
+    m.k0 = ~(uint64_t)rkr[0];
+    m.i0 = ~(uint64_t)rkr[2];
+    m.sh = rk_shift(m.k0, (uint64_t)rkr[1]);
+    m.shi = rk_shift(m.i0, (uint64_t)rkr[3]);
+    return m;
 }
 
-__device__ __forceinline__ void d_rk_range(const double* __restrict__ ps, const unsigned long long* __restrict__ Pp,
+__device__ __forceinline__ int rk_bucket(double s, int64_t id, const RkMap& m) {
+    return s > 0.0 ? (int)((rk_key(s) - m.k0) >> m.sh) : RK_NB / 2 + (int)(((uint64_t)id - m.i0) >> m.shi);
+}
+
+__device__ __forceinline__ void d_rk_range(const double* __restrict__ ps, const int64_t* __restrict__ pool,
+                                           const unsigned long long* __restrict__ Pp,
                                            int64_t cap, unsigned long long* __restrict__ rkr) {
     const int64_t P = min((int64_t)*Pp, cap);
-    uint64_t nk = 0, xk = 0;                               // max of ~key, max of key
+    uint64_t v[4] = {0, 0, 0, 0};                          // as rkr
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P; i += (int64_t)gridDim.x * blockDim.x) {
         const double sv = ps[i];
-        if (!(sv > 0.0)) continue;
-        const uint64_t k = rk_key(sv);
-        nk = max(nk, ~k);
-        xk = max(xk, k);
+        if (sv > 0.0) {
+            const uint64_t k = rk_key(sv);
+            v[0] = max(v[0], ~k);
+            v[1] = max(v[1], k);
+        } else {
+            const uint64_t k = (uint64_t)pool[i];
+            v[2] = max(v[2], ~k);
+            v[3] = max(v[3], k);
+        }
     }
-    for (int o = 32; o > 0; o >>= 1) {
-        nk = max(nk, (uint64_t)__shfl_xor((unsigned long long)nk, o, 64));
-        xk = max(xk, (uint64_t)__shfl_xor((unsigned long long)xk, o, 64));
-    }
-    if ((threadIdx.x & 63) == 0 && (nk | xk)) {
-        atomicMax(&rkr[0], (unsigned long long)nk);
-        atomicMax(&rkr[1], (unsigned long long)xk);
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        for (int o = 32; o > 0; o >>= 1) v[q] = max(v[q], (uint64_t)__shfl_xor((unsigned long long)v[q], o, 64));
+        if ((threadIdx.x & 63) == 0 && v[q]) atomicMax(&rkr[q], (unsigned long long)v[q]);
     }
 }
 
-__device__ __forceinline__ void d_rk_hist(const double* __restrict__ ps, const unsigned long long* __restrict__ Pp,
+__device__ __forceinline__ void d_rk_hist(const double* __restrict__ ps, const int64_t* __restrict__ pool,
+                                          const unsigned long long* __restrict__ Pp,
                                           int64_t cap, const unsigned long long* __restrict__ rkr,
                                           uint32_t* __restrict__ rkh) {
     const int64_t P = min((int64_t)*Pp, cap);
-    uint64_t k0;
-    int sh;
-    rk_range(rkr, k0, sh);
+    const RkMap m = rk_map(rkr);
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P; i += (int64_t)gridDim.x * blockDim.x)
-        atomicAdd(&rkh[rk_bucket(ps[i], k0, sh)], 1u);
+        atomicAdd(&rkh[rk_bucket(ps[i], pool[i], m)], 1u);
 }
 
 // Exclusive prefix sum of the bucket counts, in place (one block of 1024).
@@ -1758,15 +1776,14 @@ __device__ __forceinline__ void d_rk_scan(uint32_t* __restrict__ rkh) {
 }
 
 // Entries grouped by bucket: after this rkh[b] is the end of bucket b.
-__device__ __forceinline__ void d_rk_scatter(const double* __restrict__ ps, const unsigned long long* __restrict__ Pp,
+__device__ __forceinline__ void d_rk_scatter(const double* __restrict__ ps, const int64_t* __restrict__ pool,
+                                             const unsigned long long* __restrict__ Pp,
                                              int64_t cap, const unsigned long long* __restrict__ rkr,
                                              uint32_t* __restrict__ rkh, int32_t* __restrict__ byb) {
     const int64_t P = min((int64_t)*Pp, cap);
-    uint64_t k0;
-    int sh;
-    rk_range(rkr, k0, sh);
+    const RkMap m = rk_map(rkr);
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P; i += (int64_t)gridDim.x * blockDim.x)
-        byb[atomicAdd(&rkh[rk_bucket(ps[i], k0, sh)], 1u)] = (int32_t)i;
+        byb[atomicAdd(&rkh[rk_bucket(ps[i], pool[i], m)], 1u)] = (int32_t)i;
 }
 
 __device__ __forceinline__ void d_rk_rank(const double* __restrict__ ps, const int64_t* __restrict__ pool,
@@ -1775,13 +1792,11 @@ __device__ __forceinline__ void d_rk_rank(const double* __restrict__ ps, const i
                                           const uint32_t* __restrict__ rkh, const int32_t* __restrict__ byb,
                                           int32_t* __restrict__ rank) {
     const int64_t P = min((int64_t)*Pp, cap);
-    uint64_t k0;
-    int sh;
-    rk_range(rkr, k0, sh);
+    const RkMap m = rk_map(rkr);
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P; i += (int64_t)gridDim.x * blockDim.x) {
         const double si = ps[i];
         const long long ii = (long long)pool[i];
-        const int b = rk_bucket(si, k0, sh);
+        const int b = rk_bucket(si, ii, m);
         const uint32_t b0 = b ? rkh[b - 1] : 0u, b1 = rkh[b];
         int c = 0;
         for (uint32_t q = b0; q < b1; q++) {
@@ -2430,12 +2445,12 @@ __global__ __launch_bounds__(256) void k_rankp(ctab<SelArgs> A) {
 
 __global__ __launch_bounds__(256) void k_rk_range(ctab<SelArgs> A) {
     const SelArgs& a = tab(A, blockIdx.y);
-    d_rk_range(a.ps, a.cnt, a.cap, a.rkr);
+    d_rk_range(a.ps, a.pool, a.cnt, a.cap, a.rkr);
 }
 
 __global__ __launch_bounds__(256) void k_rk_hist(ctab<SelArgs> A) {
     const SelArgs& a = tab(A, blockIdx.y);
-    d_rk_hist(a.ps, a.cnt, a.cap, a.rkr, a.rkh);
+    d_rk_hist(a.ps, a.pool, a.cnt, a.cap, a.rkr, a.rkh);
 }
 
 __global__ __launch_bounds__(1024) void k_rk_scan(ctab<SelArgs> A) {
@@ -2445,7 +2460,7 @@ __global__ __launch_bounds__(1024) void k_rk_scan(ctab<SelArgs> A) {
 
 __global__ __launch_bounds__(256) void k_rk_scatter(ctab<SelArgs> A) {
     const SelArgs& a = tab(A, blockIdx.y);
-    d_rk_scatter(a.ps, a.cnt, a.cap, a.rkr, a.rkh, a.lo);
+    d_rk_scatter(a.ps, a.pool, a.cnt, a.cap, a.rkr, a.rkh, a.lo);
 }
 
 __global__ __launch_bounds__(256) void k_rk_rank(ctab<SelArgs> A) {
