@@ -481,6 +481,38 @@ def test_screen_degenerate_inputs(torch, ctx, D, oracle_mod, seed, p, n, R, fixc
                                atol=1e-14 * float(np.max(np.abs(V))))
 
 
+@pytest.mark.parametrize("seed,p,n,R,big", [(4, 7, 96, 3, 400.0), (5, 7, 75, 3, 1e7), (6, 6, 64, 2, 1e7)])
+def test_screen_degenerate_inputs_bf16(torch, ctx, D, oracle_mod, seed, p, n, R, big):
+    """The same degenerate primaries through the BF16 precision form: the
+    rung-3 products on the matrix cores with their range checks (a column of
+    magnitude 1e7 puts rung-3 values beyond the FP32 limits, which must go
+    to the exact fix-up), the rung-2 BF16 pair tiles, and the exact rescore
+    of the guard band reproduce the oracle's counts and selection."""
+    import synth
+    O = oracle_mod
+    rng = np.random.default_rng(700 + seed)
+    X = _degenerate_X(rng, p, n)
+    X[3] = X[3] / 400.0 * big
+    y = X[0] * np.abs(X[1]) + 0.5 * np.exp(-X[0]) + 0.01 * rng.normal(size=n)
+    if R == 3:
+        sp = O.Space(p, 3, O.OPS, rung_ops=(None, None, None, synth.BINARY_OPS),
+                     rung_pool=(None, None, None, 0))
+        prm = D.params(rung=3, k=30, rung_ops=(None, None, None, synth.BINARY_OPS),
+                       rung_pool=(None, None, None, 0), precision=D.BF16_GUARD)
+    else:
+        sp = O.Space(p, R, O.OPS)
+        prm = D.params(rung=R, k=30, precision=D.BF16_GUARD, lp_pairs=1)
+    (lst,), status, nvalid = O.sis(sp, X, None, y[None], 30, (), "per_target", True)
+    counts = status if len(status) == 5 else np.bincount(status, minlength=5)
+    assert counts[O.ST_NONFINITE] > 0
+    ids, sc, vals, st = ctx.generate_screen(dev(torch, X), dev(torch, y[None]), prm)
+    check_selection(ids[0].cpu().numpy(), sc[0].cpu().numpy(), lst[0], lst[1],
+                    what="degenerate bf16 seed %d" % seed)
+    assert st["n_unit_valid"] == sp.N - int(counts[O.ST_UNIT])
+    assert st["n_scored"] == nvalid, (st["n_scored"], nvalid)
+    assert st["max_lowprec_err"] <= st["guard_band"]
+
+
 def test_sisso_degenerate_inputs(torch, ctx, D, oracle_mod):
     """The whole loop (screen, L0 D <= 2, residuals) on the degenerate
     primaries, rung 2."""
