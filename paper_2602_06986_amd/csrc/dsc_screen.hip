@@ -1671,10 +1671,12 @@ __device__ __forceinline__ void d_rankp(const double* __restrict__ ps, const int
 
 // Large pools: ranks of the pool by (-score, ID) through buckets: an entry
 // with a positive score goes to one of the first RK_NB / 2 buckets by its
-// order key relative to the smallest key (the keys are monotone in -score,
-// and a shift spreads their range over the buckets), an entry scored -1 to
-// one of the last RK_NB / 2 by its ID relative to the smallest such ID (the
-// order among equal scores).  A bucket's entries all precede the next
+// distance below the largest score, scaled so that the smallest positive
+// score lands in the last of them (rounding is monotone, so a higher score
+// never lands in a later bucket; scores are at most 1, so a stray tiny score
+// only narrows the scale), an entry scored -1 to one of the last RK_NB / 2
+// by its ID relative to the smallest such ID (the order among equal
+// scores).  A bucket's entries all precede the next
 // bucket's, so an entry's rank is the number of entries in earlier buckets
 // (a prefix sum of the bucket counts) plus the number of its bucket-mates
 // it follows (the same comparison as count_before).  The work is O(P) plus
@@ -1683,19 +1685,14 @@ __device__ __forceinline__ void d_rankp(const double* __restrict__ ps, const int
 constexpr int RK_NB = 65536;
 constexpr int64_t RANK_PAIRS_MAX = 16384;   // pool capacity up to which all pairs are counted
 
-__device__ __forceinline__ uint64_t rk_key(double s) {
-    uint64_t u = (uint64_t)__double_as_longlong(s);
-    u = (u >> 63) ? ~u : (u | 0x8000000000000000ull);     // increasing with s
-    return ~u;                                             // increasing with -s
-}
-
-// The buckets' origins and shifts: rkr[0] / rkr[1] hold the complement of
-// the smallest and the largest key of the positive scores, rkr[2] / rkr[3]
-// the complement of the smallest and the largest ID of the entries scored
-// -1 (all start at 0).
+// The buckets' scales: rkr[0] / rkr[1] hold the complement of the bits of
+// the smallest and the bits of the largest positive score (positive
+// doubles order as their bits), rkr[2] / rkr[3] the complement of the
+// smallest and the largest ID of the entries scored -1 (all start at 0).
 struct RkMap {
-    uint64_t k0, i0;
-    int sh, shi;
+    double smax, inv;
+    uint64_t i0;
+    int shi;
 };
 
 __device__ __forceinline__ int rk_shift(uint64_t lo, uint64_t hi) {
@@ -1707,15 +1704,17 @@ __device__ __forceinline__ int rk_shift(uint64_t lo, uint64_t hi) {
 
 __device__ __forceinline__ RkMap rk_map(const unsigned long long* __restrict__ rkr) {
     RkMap m;
-    m.k0 = ~(uint64_t)rkr[0];
+    const double smin = __longlong_as_double((long long)~rkr[0]);
+    m.smax = __longlong_as_double((long long)rkr[1]);
+    m.inv = m.smax > smin ? (double)(RK_NB / 2 - 1) / (m.smax - smin) : 0.0;
     m.i0 = ~(uint64_t)rkr[2];
-    m.sh = rk_shift(m.k0, (uint64_t)rkr[1]);
     m.shi = rk_shift(m.i0, (uint64_t)rkr[3]);
     return m;
 }
 
 __device__ __forceinline__ int rk_bucket(double s, int64_t id, const RkMap& m) {
-    return s > 0.0 ? (int)((rk_key(s) - m.k0) >> m.sh) : RK_NB / 2 + (int)(((uint64_t)id - m.i0) >> m.shi);
+    return s > 0.0 ? min(RK_NB / 2 - 1, (int)((m.smax - s) * m.inv))
+                   : RK_NB / 2 + (int)(((uint64_t)id - m.i0) >> m.shi);
 }
 
 __device__ __forceinline__ void d_rk_range(const double* __restrict__ ps, const int64_t* __restrict__ pool,
@@ -1726,7 +1725,7 @@ __device__ __forceinline__ void d_rk_range(const double* __restrict__ ps, const 
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P; i += (int64_t)gridDim.x * blockDim.x) {
         const double sv = ps[i];
         if (sv > 0.0) {
-            const uint64_t k = rk_key(sv);
+            const uint64_t k = (uint64_t)__double_as_longlong(sv);
             v[0] = max(v[0], ~k);
             v[1] = max(v[1], k);
         } else {
