@@ -1900,8 +1900,61 @@ __device__ __forceinline__ bool dup_pair(const int64_t* __restrict__ pool, int32
     return fabs(uv) / sqrt(uu * vv) >= 1.0 - TAU_DUP;
 }
 
+// The first q in [start, end) where pred holds, else end, found by the
+// whole block in strides of its size (every thread calls it; slot is a
+// shared int64 the search may use).
+template <class Pred>
+__device__ __forceinline__ int64_t block_first(int64_t start, int64_t end, Pred pred, int64_t& slot) {
+    for (int64_t base = start; base < end; base += blockDim.x) {
+        __syncthreads();
+        if (threadIdx.x == 0) slot = end;
+        __syncthreads();
+        const int64_t q = base + threadIdx.x;
+        if (q < end && pred(q)) atomicMin((unsigned long long*)&slot, (unsigned long long)q);
+        __syncthreads();
+        const int64_t f = slot;
+        if (f < end) return f;
+    }
+    return end;
+}
+
+// First heads of the listed clusters, over the whole grid: a cluster's
+// first entry always heads a group (no earlier entry can reach it), and
+// takes every entry of its near-tie window that is its duplicate (all are
+// free before it).  Work items are (cluster, slice of its window): the
+// slices of one large group of equal scores run in many blocks instead of
+// one.  The comparison is dup_pair's, the one the group pass below uses.
+constexpr int DEDUP_SLICES = 16;
+
+__device__ __forceinline__ void d_dedup_first(const int64_t* __restrict__ pool, const int32_t* __restrict__ order,
+                                              const double* __restrict__ ss,
+                                              const unsigned long long* __restrict__ Pp, int64_t cap,
+                                              const EvalCtx& ev, Ops o, int n, int32_t* __restrict__ parent,
+                                              const int32_t* __restrict__ starts,
+                                              const unsigned long long* __restrict__ ncl, const PoolVals& pvs) {
+    const int64_t P = min((int64_t)*Pp, cap);
+    const int64_t nc = (int64_t)*ncl;
+    const int w = wave_id(), nw = blockDim.x / 64;
+    const int lane = threadIdx.x & 63;
+    for (int64_t item = blockIdx.x; item < nc * DEDUP_SLICES; item += gridDim.x) {
+        const int64_t h = starts[item / DEDUP_SLICES];
+        const int sl = (int)(item % DEDUP_SLICES);
+        const double sh = ss[h];
+        const int32_t ih = order[h];
+        for (int64_t q = h + 1 + (int64_t)sl * nw + w; q < P; q += (int64_t)DEDUP_SLICES * nw) {
+            if (!(sh - ss[q] <= TAU_NEAR * sh)) break;      // past the window (scores sorted)
+            if (parent[q] != (int32_t)q) continue;
+            const bool dup = dup_pair(pool, ih, order[q], ev, o, n, pvs);
+            if (dup && lane == 0) parent[q] = (int32_t)h;
+        }
+    }
+}
+
 // Duplicate heads of the listed clusters, one cluster at a time per block
-// (blocks stride over the list).  Inside a cluster the entries are visited
+// (blocks stride over the list), after the first-head pass: a cluster's
+// first head has taken its duplicates, and the block goes on from the
+// cluster's first free entry (the cluster's end and the next free entry are
+// found by the whole block).  Inside a cluster the entries are visited
 // in sorted order: an entry that no earlier head took is a head, and takes
 // every later entry of its near-tie window (ss[h] - ss[q] <= TAU_NEAR ss[h])
 // that is still free and is its duplicate.  So each entry joins the
@@ -1932,15 +1985,14 @@ __device__ __forceinline__ void d_dedup(const int64_t* __restrict__ pool, const 
     volatile int32_t* vpar = parent;
     auto stored = [&](int32_t i) { return i < pvs.cap && !isnan(pvs.sxx[i]); };
     for (int64_t c = blockIdx.x; c < nc; c += gridDim.x) {
-        if (threadIdx.x == 0) {
-            const int64_t c0 = starts[c];
-            int64_t c1 = c0 + 1;
-            while (c1 < P && chained(ss, c1)) c1++;
-            s_c1 = c1;
-            s_head = c0;
-        }
+        const int64_t c0 = starts[c];
+        // the cluster's end, and its first entry the first-head pass left
+        // free (that pass took the first head's duplicates)
+        const int64_t c1 = block_first(c0 + 1, P, [&](int64_t q) { return !chained(ss, q); }, s_c1);
+        const int64_t h1 = block_first(c0 + 1, c1, [&](int64_t q) { return vpar[q] == (int32_t)q; }, s_head);
         __syncthreads();
-        const int64_t c1 = s_c1;
+        if (threadIdx.x == 0) s_head = h1;
+        __syncthreads();
         for (;;) {
             const int64_t h = s_head;
             if (h >= c1) break;
@@ -2045,11 +2097,9 @@ __device__ __forceinline__ void d_dedup(const int64_t* __restrict__ pool, const 
             }
             __threadfence_block();
             __syncthreads();
-            if (threadIdx.x == 0) {              // the next free entry heads the next group
-                int64_t q = h + 1;
-                while (q < c1 && vpar[q] != (int32_t)q) q++;
-                s_head = q;
-            }
+            // the next free entry heads the next group
+            const int64_t hn = block_first(h + 1, c1, [&](int64_t q) { return vpar[q] == (int32_t)q; }, s_end);
+            if (threadIdx.x == 0) s_head = hn;
             __syncthreads();
         }
     }
@@ -2480,6 +2530,11 @@ __global__ __launch_bounds__(256) void k_clusters(ctab<SelArgs> A) {
 }
 
 constexpr int DEDUP_THREADS = 512;
+
+__global__ __launch_bounds__(256) void k_dedup_first(ctab<SelArgs> A) {
+    const SelArgs& a = tab(A, blockIdx.y);
+    d_dedup_first(a.pool, a.order, a.ss, a.cnt, a.cap, a.ev, a.o, a.n, a.parent, a.wc, a.ncl, a.pvs);
+}
 
 __global__ __launch_bounds__(DEDUP_THREADS) void k_dedup(ctab<SelArgs> A) {
     const SelArgs& a = tab(A, blockIdx.y);
@@ -3498,6 +3553,7 @@ static void select_round(discover_ctx* ctx, const discover_problem* probs,
     }
     if (prm.dedup) {
         KTimer kt(ctx, st, "dedup_pairs");
+        k_dedup_first<<<dim3((unsigned)std::max(256, 4096 / nl), nl), 256, 0, st>>>(dsa);
         k_dedup<<<dim3((unsigned)std::max(64, 1024 / nl), nl), DEDUP_THREADS, 0, st>>>(dsa);
         check_launch("k_dedup");
     }
