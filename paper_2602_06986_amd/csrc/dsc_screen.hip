@@ -1785,6 +1785,11 @@ __device__ __forceinline__ void d_rk_scatter(const double* __restrict__ ps, cons
         byb[atomicAdd(&rkh[rk_bucket(ps[i], pool[i], m)], 1u)] = (int32_t)i;
 }
 
+// Ranks in bucket order: a block takes 256 consecutive positions of the
+// bucket-grouped list, stages the entries of the buckets they touch (256 at
+// a time, in LDS) and each thread counts its bucket-mates before it, so a
+// bucket of many equal scores is compared from LDS rather than by one
+// thread's chain of loads.
 __device__ __forceinline__ void d_rk_rank(const double* __restrict__ ps, const int64_t* __restrict__ pool,
                                           const unsigned long long* __restrict__ Pp, int64_t cap,
                                           const unsigned long long* __restrict__ rkr,
@@ -1792,18 +1797,52 @@ __device__ __forceinline__ void d_rk_rank(const double* __restrict__ ps, const i
                                           int32_t* __restrict__ rank) {
     const int64_t P = min((int64_t)*Pp, cap);
     const RkMap m = rk_map(rkr);
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P; i += (int64_t)gridDim.x * blockDim.x) {
-        const double si = ps[i];
-        const long long ii = (long long)pool[i];
-        const int b = rk_bucket(si, ii, m);
-        const uint32_t b0 = b ? rkh[b - 1] : 0u, b1 = rkh[b];
-        int c = 0;
-        for (uint32_t q = b0; q < b1; q++) {
-            const int32_t j = byb[q];
-            const double sj = ps[j];
-            c += (int)(sj > si) | ((int)(sj == si) & (int)((long long)pool[j] < ii));
+    __shared__ double ts[256];
+    __shared__ long long tk[256];
+    __shared__ uint32_t s_lo, s_hi;
+    for (int64_t q0 = (int64_t)blockIdx.x * 256; q0 < P; q0 += (int64_t)gridDim.x * 256) {
+        const int64_t q = q0 + threadIdx.x;
+        const bool has = q < P;
+        const int32_t i = has ? byb[q] : 0;
+        const double si = has ? ps[i] : 0.0;
+        const long long ii = has ? (long long)pool[i] : 0;
+        uint32_t b0 = 0, b1 = 0;
+        if (has) {
+            const int b = rk_bucket(si, ii, m);
+            b0 = b ? rkh[b - 1] : 0u;
+            b1 = rkh[b];
         }
-        rank[i] = (int32_t)(b0 + c);
+        if (threadIdx.x == 0) {
+            s_lo = 0xFFFFFFFFu;
+            s_hi = 0u;
+        }
+        __syncthreads();
+        if (has) {
+            atomicMin(&s_lo, b0);
+            atomicMax(&s_hi, b1);
+        }
+        __syncthreads();
+        const uint32_t lo = s_lo, hi = s_hi;
+        int c = 0;
+        for (uint32_t t0 = lo; t0 < hi; t0 += 256) {
+            __syncthreads();
+            const uint32_t j = t0 + threadIdx.x;
+            if (j < hi) {
+                const int32_t jj = byb[j];
+                ts[threadIdx.x] = ps[jj];
+                tk[threadIdx.x] = (long long)pool[jj];
+            }
+            __syncthreads();
+            const uint32_t lim = min(256u, hi - t0);
+            if (has)
+                for (uint32_t k = 0; k < lim; k++) {
+                    const uint32_t pos = t0 + k;
+                    const bool mate = pos >= b0 && pos < b1;
+                    c += (int)mate & ((int)(ts[k] > si) | ((int)(ts[k] == si) & (int)(tk[k] < ii)));
+                }
+        }
+        if (has) rank[i] = (int32_t)(b0 + c);
+        __syncthreads();                                   // s_lo, s_hi are set again
     }
 }
 
