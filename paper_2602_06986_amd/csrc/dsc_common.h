@@ -416,8 +416,16 @@ static __global__ __launch_bounds__(256) void k_fill(ctab<FillSeg> segs) {
     const FillSeg& f = tab(segs, blockIdx.y);
     uint32_t* p = (uint32_t*)f.p;
     DSC_GLOBAL(p);
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < f.n32; i += (int64_t)gridDim.x * 256)
-        p[i] = f.v;
+    const int64_t t0 = (int64_t)blockIdx.x * 256 + threadIdx.x, stride = (int64_t)gridDim.x * 256;
+    if (((uintptr_t)p & 15) == 0) {                       // 16-byte stores, then the tail
+        const int64_t n4 = f.n32 >> 2;
+        uint4* q = (uint4*)p;
+        const uint4 v = make_uint4(f.v, f.v, f.v, f.v);
+        for (int64_t i = t0; i < n4; i += stride) q[i] = v;
+        for (int64_t i = 4 * n4 + t0; i < f.n32; i += stride) p[i] = f.v;
+    } else {
+        for (int64_t i = t0; i < f.n32; i += stride) p[i] = f.v;
+    }
 }
 
 // Launch the fills of `segs` (each size a multiple of 4 bytes).
@@ -427,7 +435,7 @@ inline void fill_all(discover_ctx* ctx, const std::string& name, const std::vect
     int64_t mx = 1;
     for (const FillSeg& f : segs) mx = std::max<int64_t>(mx, f.n32);
     const FillSeg* d = ctx->upload(name, segs, st);
-    dim3 g((unsigned)std::min<int64_t>(256, cdiv(mx, 256)), (unsigned)segs.size());
+    dim3 g((unsigned)std::min<int64_t>(2048, cdiv(mx, 1024)), (unsigned)segs.size());
     k_fill<<<g, 256, 0, st>>>(ct(d));
     check_launch("k_fill");
 }
