@@ -2458,11 +2458,21 @@ struct FixArgs {
 };
 
 // grid (persistent blocks, problems)
+// TM: the most targets of any problem of the launch (1, 8 or 16).
+template <int TM>
 __global__ __launch_bounds__(256) void k_fixup(ctab<FixArgs> A) {
     const FixArgs& a = tab(A, blockIdx.y);
     DSC_GLOBAL(a.ids); DSC_GLOBAL(a.cnt); DSC_GLOBAL(a.ev.raw2c); DSC_GLOBAL(a.ev.valid); DSC_GLOBAL(a.o.Vf); DSC_GLOBAL(a.o.Rf); DSC_GLOBAL(a.Yc); DSC_GLOBAL(a.syy); DSC_GLOBAL(a.scores); DSC_GLOBAL(a.nscored);
-    d_fixup<DISCOVER_MAX_TARGETS>(a.ids, a.cnt, a.cap, a.ev, a.o, a.n, a.T, a.mode, a.Yc, a.syy, a.N,
+    d_fixup<TM>(a.ids, a.cnt, a.cap, a.ev, a.o, a.n, a.T, a.mode, a.Yc, a.syy, a.N,
                                   a.scores, a.nscored, a.r2v, a.r2m, a.r2q);
+}
+
+static void launch_fixup(const std::vector<FixArgs>& fa, dim3 grid, ctab<FixArgs> d, hipStream_t st) {
+    int Tm = 1;
+    for (const FixArgs& x : fa) Tm = std::max(Tm, x.T);
+    if (Tm <= 1) k_fixup<1><<<grid, 256, 0, st>>>(d);
+    else if (Tm <= 8) k_fixup<8><<<grid, 256, 0, st>>>(d);
+    else k_fixup<DISCOVER_MAX_TARGETS><<<grid, 256, 0, st>>>(d);
 }
 
 // Everything the exact top-k of one list (problem, target) works on.
@@ -3353,7 +3363,7 @@ static void screen_all(discover_ctx* ctx, const discover_problem* probs, int nb,
     {
         KTimer kt(ctx, st, "screen_fixup");
         const unsigned fb = (unsigned)std::max(1, std::min(1024, 4096 / nb));
-        k_fixup<<<dim3(fb, nb), 256, 0, st>>>(ct(ctx->upload("scr_fix", fa, st)));
+        launch_fixup(fa, dim3(fb, nb), ct(ctx->upload("scr_fix", fa, st)), st);
         check_launch("k_fixup");
     }
     // 8. operator-limited rung 3 on top of the rung-2 operand statistics
@@ -3383,7 +3393,7 @@ static void screen_all(discover_ctx* ctx, const discover_problem* probs, int nb,
     }
     if (!fa3.empty()) {
         KTimer kt(ctx, st, "screen_fixup");
-        k_fixup<<<dim3(1024, (unsigned)fa3.size()), 256, 0, st>>>(ct(ctx->upload("scr_fix3", fa3, st)));
+        launch_fixup(fa3, dim3(1024, (unsigned)fa3.size()), ct(ctx->upload("scr_fix3", fa3, st)), st);
         check_launch("k_fixup");
     }
 }
