@@ -40,6 +40,7 @@ struct R3Plan {
     int n_as_ctiles = 0;
     int2* as_work = nullptr;
     int64_t n_as_work = 0;
+    int32_t* as_gidx = nullptr;       // per add/sub record: its index in grec (score slots)
     uint32_t ops = 0;                 // rung-3 binary operators (bit o - OP_ADD)
     int pe = 0;                       // partner pool size (compact 0..pe-1)
     std::vector<void*> allocs;
@@ -84,10 +85,11 @@ struct R3Launch {
     const uint8_t* r2v;
     const double *r2m, *r2q;
     SpaceDev sd;
-    int64_t N;
+    SlotMap sm;                       // score slot of each candidate
+    int64_t N;                        // slots per target
     double* scores;
     unsigned long long* nscored;
-    int64_t* fix_ids;
+    int64_t* fix_ids;                 // slots of the candidates left to the fix-up
     unsigned long long* fix_cnt;
     int64_t fix_cap;
     int precision;                    // DISCOVER_BF16_GUARD: precision form of mul/div/rdiv

@@ -249,10 +249,12 @@ struct R3mArgs {
     const uint8_t* r2v;
     const double* ysum;
     SpaceDev sd;
+    SlotMap sm;
+    const int32_t* gidx;      // add / sub: grec index of each record (score slots)
     int64_t N;
     double* scores;
     unsigned long long* nscored;
-    int64_t* fix_ids;
+    int64_t* fix_ids;         // score slots
     unsigned long long* fix_cnt;
     int64_t fix_cap;
 };
@@ -397,7 +399,6 @@ __global__ __launch_bounds__(256) void k_r3_mm(R3mArgs g) {
         const int32_t cd = g.coldesc[ct * 16 + r16];
         const int p = cd & 0xFFFF;
         const bool colok = cd >= 0 && (cd >> 16) == 0 && g.valid[p];
-        const int64_t praw = colok ? g.mat_raw[p] : 0;
         const int src = (lane & 48) | 15;
 #pragma unroll
         for (int r = 0; r < 4; r++) {
@@ -408,8 +409,8 @@ __global__ __launch_bounds__(256) void k_r3_mm(R3mArgs g) {
             gs[TP] = __shfl(acc[0][TP][r], src, 64);
             gs[TP + 1] = __shfl(acc[0][TP + 1][r], src, 64);
             const bool ok = __shfl((int)rok[0], i, 64) != 0 && colok;
-            const int64_t gj = __shfl(j2[0], i, 64);
             if (!ok) continue;
+            const int64_t gr = g.gidx[tile0 * 16 + i];  // the row's rung-2 record
             const double* pc = g.pconst + (int64_t)p * TK;
             const double Sxg = acc[0][TP][r];
             const double A = pc[TP + 1] + gs[TP + 1];
@@ -417,7 +418,7 @@ __global__ __launch_bounds__(256) void k_r3_mm(R3mArgs g) {
             for (int o = 0; o < 2; o++) {
                 if (!((g.ops >> o) & 1u)) continue;
                 const double sg = o == 0 ? 1.0 : -1.0;
-                const int64_t id = pair_id(g.sd, 3, OP_ADD + o, praw, gj);
+                const int64_t id = slot3(g.sm, OP_ADD + o, gr, p);
                 const double S1 = pc[TP] + sg * gs[TP];
                 const double S2 = pc[TP + 1] + 2.0 * sg * Sxg + gs[TP + 1];
                 const double varn = S2 - S1 * (S1 / nn);
@@ -449,17 +450,15 @@ __global__ __launch_bounds__(256) void k_r3_mm(R3mArgs g) {
         const int op3 = kind == 0 ? OP_MUL : kind == 1 ? OP_RDIV : OP_DIV;
         const bool colok = cd >= 0 && ((g.ops >> (op3 - OP_ADD)) & 1u) && g.valid[p];
         const double xmx = colok ? g.pstat[p] : 0.0, xmn = colok ? g.pstat[g.pe + p] : 1.0;
-        const int64_t praw = colok ? g.mat_raw[p] : 0;
     #pragma unroll
         for (int u = 0; u < GT; u++) {
     #pragma unroll
             for (int r = 0; r < 4; r++) {
                 const int i = kq + 4 * r;                      // row of this register
                 const bool ok = __shfl((int)rok[u], i, 64) != 0 && colok;
-                const int64_t gj = __shfl(j2[u], i, 64);
                 const double rmx = __shfl(gmx[u], i, 64), rmn = __shfl(gmn[u], i, 64);
                 if (!ok) continue;
-                const int64_t id = pair_id(g.sd, 3, op3, praw, gj);
+                const int64_t id = slot3(g.sm, op3, (tile0 + u) * 16 + i, p);   // score slot
                 // finiteness of the candidate's values
                 bool sure = true;
                 if (op3 == OP_MUL) {
@@ -828,7 +827,6 @@ __global__ __launch_bounds__(256, (TP * CT <= 16 ? 2 : 1)) void k_r3_lp(R3lpArgs
         const int op3 = kind == 0 ? OP_MUL : kind == 1 ? OP_RDIV : OP_DIV;
         const bool colok = cd >= 0 && ((g.ops >> (op3 - OP_ADD)) & 1u) && g.valid[p];
         const double xmx = colok ? g.pstat[p] : 0.0, xmn = colok ? g.pstat[g.pe + p] : 1.0;
-        const int64_t praw = colok ? g.mat_raw[p] : 0;
         double S1[4], S2[4];                             // row 4 kq + e in slot e
 #pragma unroll
         for (int e = 0; e < 4; e++) {
@@ -848,7 +846,7 @@ __global__ __launch_bounds__(256, (TP * CT <= 16 ? 2 : 1)) void k_r3_lp(R3lpArgs
             // |1/g| (div tiles only)
             const double rmx = sqrt(nn * a.r2q[gj - g.sd.off[2]]) * 1.01;
             const double rmn = hk ? 1.0 / hx : 0.0;
-            const int64_t id = pair_id(g.sd, 3, op3, praw, gj);
+            const int64_t id = slot3(g.sm, op3, tile0 * 16 + i, p);   // score slot
             bool sure;
             double amx, fmx, bmx;                          // largest |A|, |f|, |B| of the products
             if (op3 == OP_MUL) {
@@ -1015,6 +1013,7 @@ std::shared_ptr<R3Plan> build_r3_plan(const Space& sp, uint32_t r3_ops) {
         pad16(o);
     }
     P->n_grec = (int64_t)rec.size();
+    DSC_REQUIRE(P->n_grec < ((int64_t)1 << 31), "rung-3 record list too large");
     // partner column tiles: per group of 8 partners, 8 mul then 8 rdiv
     // columns (both against g); then the div columns (against 1/g)
     const bool mul = (r3_ops >> (OP_MUL - OP_ADD)) & 1u, div = (r3_ops >> (OP_DIV - OP_ADD)) & 1u,
@@ -1036,10 +1035,8 @@ std::shared_ptr<R3Plan> build_r3_plan(const Space& sp, uint32_t r3_ops) {
     }
     P->n_ctiles = (int)(cols.size() / 16);
     P->h_coldesc = cols;
-    if (P->n_grec && P->n_ctiles) {
-        P->grec = r3_up(*P, rec);
-        P->coldesc = r3_up(*P, cols);
-    }
+    if (P->n_grec) P->grec = r3_up(*P, rec);            // also what the score slots decode
+    if (P->n_grec && P->n_ctiles) P->coldesc = r3_up(*P, cols);
     // add / sub: records grouped by unit vector and operator, against
     // column tiles of the partners with the same unit vector (15 at most)
     // and a column of ones
@@ -1054,7 +1051,7 @@ std::shared_ptr<R3Plan> build_r3_plan(const Space& sp, uint32_t r3_ops) {
             if (pg.count(kk)) byk[kk][(int)((unsigned)rec[r].y >> 28)].push_back(r);
         }
         std::vector<int2> arec, work;
-        std::vector<int32_t> acols;
+        std::vector<int32_t> acols, agidx;
         for (auto& e : byk) {
             const std::vector<int32_t>& pl = pg[e.first];
             const int ct0 = (int)(acols.size() / 16);
@@ -1065,8 +1062,14 @@ std::shared_ptr<R3Plan> build_r3_plan(const Space& sp, uint32_t r3_ops) {
             const int ct1 = (int)(acols.size() / 16);
             for (auto& ro : e.second) {
                 const int64_t rt0 = (int64_t)arec.size() / 16;
-                for (int64_t r : ro.second) arec.push_back(rec[r]);
-                while (arec.size() % 16) arec.push_back(make_int2(-2, ro.first << 28));
+                for (int64_t r : ro.second) {
+                    arec.push_back(rec[r]);
+                    agidx.push_back((int32_t)r);
+                }
+                while (arec.size() % 16) {
+                    arec.push_back(make_int2(-2, ro.first << 28));
+                    agidx.push_back(0);
+                }
                 const int64_t rt1 = (int64_t)arec.size() / 16;
                 for (int64_t rt = rt0; rt < rt1; rt++)
                     for (int c = ct0; c < ct1; c++) work.push_back(make_int2((int)rt, c));
@@ -1080,6 +1083,7 @@ std::shared_ptr<R3Plan> build_r3_plan(const Space& sp, uint32_t r3_ops) {
             P->as_grec = r3_up(*P, arec);
             P->as_coldesc = r3_up(*P, acols);
             P->as_work = r3_up(*P, work);
+            P->as_gidx = r3_up(*P, agidx);
         }
     }
     return P;
@@ -1104,7 +1108,7 @@ void launch_r3(discover_ctx* ctx, const R3Launch& a, hipStream_t st) {
         m.NQ = NQ; m.n = a.n; m.T = a.T; m.mode = a.mode; m.ldn = a.ldn; m.bmat = a.bmat;
         m.Vf = a.Vf; m.Rf = a.Rf; m.pstat = a.pstat; m.pe = P.pe; m.ops = P.ops;
         m.valid = a.valid; m.mat_raw = a.mat_raw; m.r2v = a.r2v; m.ysum = a.ysum; m.sd = a.sd;
-        m.N = a.N; m.scores = a.scores; m.nscored = a.nscored; m.fix_ids = a.fix_ids;
+        m.sm = a.sm; m.N = a.N; m.scores = a.scores; m.nscored = a.nscored; m.fix_ids = a.fix_ids;
         m.fix_cnt = a.fix_cnt; m.fix_cap = a.fix_cap;
         l.b32 = b32; l.blp = blp; l.r2q = a.r2q; l.NC = NC; l.delta = a.delta; l.cm = r3_moment_err(a.n);
         KTimer kt(ctx, st, "screen_r3");
@@ -1128,7 +1132,7 @@ void launch_r3(discover_ctx* ctx, const R3Launch& a, hipStream_t st) {
         m.NQ = NQ; m.n = a.n; m.T = a.T; m.mode = a.mode; m.ldn = a.ldn; m.bmat = a.bmat;
         m.Vf = a.Vf; m.Rf = a.Rf; m.pstat = a.pstat; m.pe = P.pe; m.ops = P.ops;
         m.valid = a.valid; m.mat_raw = a.mat_raw; m.r2v = a.r2v; m.ysum = a.ysum; m.sd = a.sd;
-        m.N = a.N; m.scores = a.scores; m.nscored = a.nscored; m.fix_ids = a.fix_ids;
+        m.sm = a.sm; m.N = a.N; m.scores = a.scores; m.nscored = a.nscored; m.fix_ids = a.fix_ids;
         m.fix_cnt = a.fix_cnt; m.fix_cap = a.fix_cap;
         KTimer kt(ctx, st, "screen_r3");
         switch (a.TP) {
@@ -1158,11 +1162,11 @@ void launch_r3(discover_ctx* ctx, const R3Launch& a, hipStream_t st) {
         check_launch("k_r3_ybmat");
         R3mArgs m{};
         m.grec = P.as_grec; m.n_grec = P.n_as_grec; m.work = P.as_work; m.n_work = P.n_as_work;
-        m.pconst = pc; m.coldesc = P.as_coldesc; m.n_gct = 0; m.ybmat = yb;
+        m.pconst = pc; m.coldesc = P.as_coldesc; m.n_gct = 0; m.ybmat = yb; m.gidx = P.as_gidx;
         m.NQ = NQ; m.n = a.n; m.T = a.T; m.mode = a.mode; m.ldn = a.ldn; m.bmat = bm;
         m.Vf = a.Vf; m.Rf = a.Rf; m.pstat = a.pstat; m.pe = P.pe; m.ops = P.ops;
         m.valid = a.valid; m.mat_raw = a.mat_raw; m.r2v = a.r2v; m.ysum = a.ysum; m.sd = a.sd;
-        m.N = a.N; m.scores = a.scores; m.nscored = a.nscored; m.fix_ids = a.fix_ids;
+        m.sm = a.sm; m.N = a.N; m.scores = a.scores; m.nscored = a.nscored; m.fix_ids = a.fix_ids;
         m.fix_cnt = a.fix_cnt; m.fix_cap = a.fix_cap;
         KTimer kt(ctx, st, "screen_r3_addsub");
         switch (a.TP) {

@@ -277,6 +277,7 @@ struct EvalCtx {
     const int32_t* raw2c;         // raw -> compact operand index
     const uint8_t* valid;         // operand validity
     const uint8_t* r2_valid;      // stream3: validity of rung-2 features, by id - off[2]
+    SlotMap sm;                   // score slot <-> ID
 };
 
 __device__ __forceinline__ double unary_value(int op, const Ops& o, int c, int s) {
@@ -1280,7 +1281,9 @@ __device__ __forceinline__ void d_compact(const double* __restrict__ sc, int64_t
                                                  uint32_t* __restrict__ gsel,
                                                  int64_t* __restrict__ gst, double margin,
                                                  int64_t cap, int64_t* __restrict__ pool,
-                                                 unsigned long long* __restrict__ cnt, int64_t K) {
+                                                 unsigned long long* __restrict__ cnt, int64_t K,
+                                                 const SlotMap& sm, const SpaceDev& sd,
+                                                 double* __restrict__ pscr) {
     uint32_t sel[3];
     int64_t st[2];
     radix_finish1(hist, K, gsel, gst, sel, st);        // one level: a lower bound suffices here
@@ -1311,7 +1314,10 @@ __device__ __forceinline__ void d_compact(const double* __restrict__ sc, int64_t
             base = __shfl(base, 0, 64);
             if (take) {
                 const unsigned long long slot = base + __popcll(m & below);
-                if ((int64_t)slot < cap) pool[slot] = i;
+                if ((int64_t)slot < cap) {
+                    pool[slot] = slot_id(sm, sd, i);
+                    pscr[slot] = x;                       // the screening score, for the rescore
+                }
             }
         }
     }
@@ -1461,7 +1467,6 @@ __device__ __forceinline__ void d_rescore(const int64_t* __restrict__ pool,
                                                  const int64_t* __restrict__ excl, int n_excl,
                                                  double* __restrict__ ps,
                                                  uint8_t* __restrict__ pex,
-                                                 const double* __restrict__ sc_row,
                                                  double* __restrict__ perr,
                                                  int32_t* __restrict__ rank,
                                                  int32_t* __restrict__ order,
@@ -1569,14 +1574,15 @@ __device__ __forceinline__ void d_rescore(const int64_t* __restrict__ pool,
         pex[w] = (uint8_t)ex;
         rank[w] = 0;                                      // counted by k_rankp or set by k_rk_rank
         order[w] = (int32_t)w;                            // (a valid index even before the scatter)
-        const double x = sc_row[id];                      // screening-pass score
+        const double x = perr[w];                         // screening-pass score (from the compaction)
         perr[w] = s > 0.0 && x > 0.0 ? fabs(x - s) : 0.0; // its maximum is taken by k_groups
     }
     }
 }
 
 // Exact two-pass score of the candidates whose shifted one-pass moments
-// were ill-conditioned (one wave each), written back into the score slots.
+// were ill-conditioned (one wave each), written back into the score slots
+// (the list holds slots; below rung 3 a slot is the ID).
 template <int TMAX>
 __device__ __forceinline__ void d_fixup(const int64_t* __restrict__ ids,
                                                const unsigned long long* __restrict__ cnt,
@@ -1590,9 +1596,10 @@ __device__ __forceinline__ void d_fixup(const int64_t* __restrict__ ids,
     const int64_t m = min((int64_t)*cnt, cap);
     unsigned nfix = 0;                                  // counted per wave, added once
     for (int64_t w = (int64_t)blockIdx.x * 4 + wave_id(); w < m; w += (int64_t)gridDim.x * 4) {
-        const int64_t id = ids[w];
+        const int64_t sl = ids[w];                      // a score slot (rung <= 2: the ID)
+        const int64_t id = slot_id(ev.sm, ev.sd, sl);
         Cand c;
-        bool ok = cand_of_id(ev, id, c);
+        bool ok = id >= 0 && cand_of_id(ev, id, c);
         double r[TMAX], mean = 0.0, msq = 0.0;
         ok = ok && wave_exact_r<TMAX>(c, o, n, T, Yc, syy, r, &mean, &msq);
         if ((threadIdx.x & 63) != 0 || !ok) continue;
@@ -1605,9 +1612,9 @@ __device__ __forceinline__ void d_fixup(const int64_t* __restrict__ ids,
         if (mode == DISCOVER_SCORE_MAX) {
             double mx = 0.0;
             for (int t = 0; t < T; t++) mx = fmax(mx, fabs(r[t]));
-            scores[id] = mx;
+            scores[sl] = mx;
         } else {
-            for (int t = 0; t < T; t++) scores[(int64_t)t * N + id] = fabs(r[t]);
+            for (int t = 0; t < T; t++) scores[(int64_t)t * N + sl] = fabs(r[t]);
         }
     }
     if ((threadIdx.x & 63) == 0 && nfix) atomicAdd(nscored, (unsigned long long)nfix);
@@ -2501,7 +2508,7 @@ struct SelArgs {
     uint32_t* rkh;            // rank buckets: counts, then starts, then ends
     unsigned long long* rkr;  // rank buckets' key range
     double* ss;               // scores in sorted order
-    double* perr;             // |screening score - exact score| per pool entry
+    double* perr;             // per pool entry: its screening score, then |screening - exact|
     int64_t* off;
     uint8_t* flag;
     unsigned long long* ncl;  // near-tie clusters listed in wc (starts)
@@ -2521,7 +2528,7 @@ struct SelArgs {
 __global__ __launch_bounds__(256) void k_compact(ctab<SelArgs> A) {
     const SelArgs& a = tab(A, blockIdx.y);
     DSC_GLOBAL(a.sc); DSC_GLOBAL(a.sel); DSC_GLOBAL(a.st); DSC_GLOBAL(a.pool); DSC_GLOBAL(a.cnt); DSC_GLOBAL(a.ev.raw2c); DSC_GLOBAL(a.ev.valid); DSC_GLOBAL(a.o.Vf); DSC_GLOBAL(a.o.Rf); DSC_GLOBAL(a.Yc); DSC_GLOBAL(a.syy); DSC_GLOBAL(a.ps); DSC_GLOBAL(a.pex); DSC_GLOBAL(a.maxerr); DSC_GLOBAL(a.order); DSC_GLOBAL(a.lo); DSC_GLOBAL(a.wc); DSC_GLOBAL(a.off); DSC_GLOBAL(a.flag); DSC_GLOBAL(a.parent); DSC_GLOBAL(a.blk); DSC_GLOBAL(a.repid); DSC_GLOBAL(a.reppos); DSC_GLOBAL(a.headpos); DSC_GLOBAL(a.out_ids); DSC_GLOBAL(a.out_sc); DSC_GLOBAL(a.res);
-    d_compact(a.sc, a.N, a.hist, a.sel, a.st, a.margin, a.cap, a.pool, a.cnt, a.K);
+    d_compact(a.sc, a.N, a.hist, a.sel, a.st, a.margin, a.cap, a.pool, a.cnt, a.K, a.ev.sm, a.ev.sd, a.perr);
 }
 
 // TM: the most targets of any list of the launch (1, 8 or 16 registers of
@@ -2531,7 +2538,7 @@ __global__ __launch_bounds__(256) void k_rescore(ctab<SelArgs> A) {
     const SelArgs& a = tab(A, blockIdx.y);
     DSC_GLOBAL(a.sc); DSC_GLOBAL(a.sel); DSC_GLOBAL(a.st); DSC_GLOBAL(a.pool); DSC_GLOBAL(a.cnt); DSC_GLOBAL(a.ev.raw2c); DSC_GLOBAL(a.ev.valid); DSC_GLOBAL(a.o.Vf); DSC_GLOBAL(a.o.Rf); DSC_GLOBAL(a.Yc); DSC_GLOBAL(a.syy); DSC_GLOBAL(a.ps); DSC_GLOBAL(a.pex); DSC_GLOBAL(a.maxerr); DSC_GLOBAL(a.order); DSC_GLOBAL(a.lo); DSC_GLOBAL(a.wc); DSC_GLOBAL(a.off); DSC_GLOBAL(a.flag); DSC_GLOBAL(a.parent); DSC_GLOBAL(a.blk); DSC_GLOBAL(a.repid); DSC_GLOBAL(a.reppos); DSC_GLOBAL(a.headpos); DSC_GLOBAL(a.out_ids); DSC_GLOBAL(a.out_sc); DSC_GLOBAL(a.res);
     d_rescore<TM>(a.pool, a.cnt, a.cap, a.ev, a.o, a.n, a.T, a.mode, a.t, a.Yc, a.syy,
-                                    a.excl, a.n_excl, a.ps, a.pex, a.sc, a.perr, a.rank, a.order, a.pvs,
+                                    a.excl, a.n_excl, a.ps, a.pex, a.perr, a.rank, a.order, a.pvs,
                                     a.rules);
 }
 
@@ -2761,6 +2768,7 @@ struct Plan {
     uint32_t list_ops = 0;
     std::shared_ptr<R3Plan> r3;               // operator-limited rung 3 work lists
     uint32_t r3_ops = 0;
+    SlotMap sm;                               // score slots of the candidates
     std::string key;
 
     template <class T>
@@ -2827,6 +2835,7 @@ static std::shared_ptr<Plan> get_plan(discover_ctx* ctx, const discover_problem&
     }
     P->items = P->up(items);
     P->n_items = (int64_t)items.size();
+    P->sm.s3 = P->sm.n = sp.n_raw();                     // slot = ID (rung 3 below)
     if (!R) return ctx->plans[key] = P, P;
     uint32_t bin = 0;
     for (int o = OP_ADD; o <= OP_RDIV; o++)
@@ -2885,6 +2894,21 @@ static std::shared_ptr<Plan> get_plan(discover_ctx* ctx, const discover_problem&
             if (sd.block[3][o] >= 0) P->r3_ops |= 1u << (o - OP_ADD);
         P->r3 = build_r3_plan(sp, P->r3_ops);
     }
+    // rung-3 slots over the plan's records (unit-legal rung-2 features)
+    if (sp.stream3 && P->r3) {
+        const R3Plan& r3 = *P->r3;
+        P->sm.s3 = sd.off[3];
+        P->sm.pe = std::max(r3.pe, 1);
+        P->sm.grec = r3.grec;
+        P->sm.mat_raw = P->mat_raw;
+        int64_t s = sd.off[3];
+        for (int q = 0; q < 5; q++)
+            if (sd.block[3][OP_ADD + q] >= 0 && r3.n_grec && r3.pe) {
+                P->sm.sblk[q] = s;
+                s += r3.n_grec * r3.pe;
+            }
+        P->sm.n = s;
+    }
     ctx->plans[key] = P;
     return P;
 }
@@ -2915,6 +2939,7 @@ struct Problem {
         e.raw2c = plan->raw2c;
         e.valid = valid;
         e.r2_valid = r2v;
+        e.sm = plan->sm;
         return e;
     }
     Ops ops() const { return Ops{Vf, Rf, ldn}; }
@@ -2955,7 +2980,7 @@ static void layout_problems(discover_ctx* ctx, const discover_problem* probs, in
         P.ldn = (int)((pb.n + 63) / 64 * 64);
         P.ldm = pl.ldm;
         P.Mc = sp.Mc();
-        P.N = sp.n_raw();
+        P.N = pl.sm.n;
         P.fix_cap = std::min<int64_t>(P.N, ctx->fix_cap_min);
         P.pairs = sp.streamed && (pl.dense_ops || pl.list_ops);
         const size_t Mc = P.Mc, ldn = P.ldn, n = P.n, ldm = P.ldm;
@@ -3379,7 +3404,7 @@ static void screen_all(discover_ctx* ctx, const discover_problem* probs, int nb,
         g3.n = P.n; g3.ldn = P.ldn; g3.TP = P.TP; g3.T = P.T; g3.mode = prm.score_mode;
         g3.Vf = P.Vf; g3.Rf = P.Rf; g3.Cf = P.Cf; g3.mu = P.mu; g3.msq = P.msq;
         g3.valid = P.valid; g3.mat_raw = pl.mat_raw; g3.Yn = P.Yn; g3.ysum = P.ysum;
-        g3.r2v = P.r2v; g3.r2m = P.r2m; g3.r2q = P.r2q; g3.sd = sd; g3.N = P.N;
+        g3.r2v = P.r2v; g3.r2m = P.r2m; g3.r2q = P.r2q; g3.sd = sd; g3.sm = pl.sm; g3.N = P.N;
         g3.scores = P.scores; g3.nscored = P.ctr + 2; g3.fix_ids = P.fix_ids3;
         g3.fix_cnt = P.ctr + 3; g3.fix_cap = P.fix_cap; g3.bmat = P.r3b; g3.pstat = P.r3p;
         // the precision form covers rung 3 in BF16 (FP16's range would need
@@ -3774,7 +3799,7 @@ static void generate_screen_once(discover_ctx* ctx, const discover_problem* prob
         const Problem& P = PS[b];
         discover_screen_stats& s = stats[b];
         s = discover_screen_stats{};
-        s.n_raw = P.N;
+        s.n_raw = P.plan->sp.n_raw();
         s.n_unit_valid = P.plan->sp.n_unit_valid;
         s.tile_j = P.tile_j;
         margin[b] = 4.0 * P.n * EPS64 * KAPPA_MAX;

@@ -74,6 +74,42 @@ __host__ __device__ inline void decode_id(const SpaceDev& s, int64_t id, int& ru
     op = OP_NONE; a = -1; b = -1;   // unreachable for valid IDs
 }
 
+// Score slots of one problem's candidates.  IDs below s3 are their own
+// slots.  With an operator-limited rung 3 only the unit-legal rung-2
+// features (the records of the rung-3 plan, padding included) get rung-3
+// slots: binary operator OP_ADD + q, record r and partner c (compact) has
+// slot sblk[q] + r pe + c.  The rung-3 slot space is then the size of the
+// unit-legal part of the rung instead of the raw one, and so are the fill,
+// histogram and compaction passes over it.
+struct SlotMap {
+    int64_t s3 = 0;           // first rung-3 slot (= first rung-3 ID)
+    int64_t n = 0;            // slots
+    int64_t sblk[5] = {-1, -1, -1, -1, -1};   // ascending where enabled, -1 disabled
+    int32_t pe = 1;           // partners
+    const int2* grec = nullptr;       // records: k (-1 unary, -2 padding), l | op2 << 28
+    const int64_t* mat_raw = nullptr; // compact -> raw operand index
+};
+
+// Rung-3 slot of (operator o, record r, partner c).
+__host__ __device__ inline int64_t slot3(const SlotMap& m, int o, int64_t r, int c) {
+    return m.sblk[o - OP_ADD] + r * m.pe + c;
+}
+
+// ID of a slot (-1 for a padding record's slot, which is never written).
+__device__ inline int64_t slot_id(const SlotMap& m, const SpaceDev& s, int64_t slot) {
+    if (slot < m.s3 || !m.grec) return slot;
+    int q = 4;
+    while (q > 0 && (m.sblk[q] < 0 || slot < m.sblk[q])) q--;
+    const int64_t w = slot - m.sblk[q];
+    const int64_t r = w / m.pe;
+    const int c = (int)(w - r * m.pe);
+    const int2 rc = m.grec[r];
+    const int k = rc.x, l = rc.y & 0x0FFFFFFF, op2 = (int)((unsigned)rc.y >> 28);
+    if (k == -2) return -1;
+    const int64_t j2 = k < 0 ? unary_id(s, 2, op2, m.mat_raw[l]) : pair_id(s, 2, op2, m.mat_raw[k], m.mat_raw[l]);
+    return pair_id(s, 3, OP_ADD + q, m.mat_raw[c], j2);
+}
+
 // Host description of one search space plus the operand features that are
 // materialised in HBM (all unit-legal features of rungs below the streamed
 // rung; for rung 0 the primaries themselves).
