@@ -53,11 +53,11 @@ SWEEP3_COUNTERS = {
 R3_COUNTERS = {
     # the precision form: totals of the k_r3_lp kernels of one dimension
     "k_r3_lp": {"source": "paper_2602_06986_amd/csrc/dsc_r3.hip",
-                "sha256": "81ba33d12238a00f2f4a824bf5b21a4e4d9f95730669143c6fba0b5f4321430d",
-                "fetch_kib": 1474688.9, "fetch_scale": 1.99992, "write_kib": 1215267.7, "write_scale": 1.0},
+                "sha256": "82721cb4e10461cbb8c43d98119a9ec1dab68aaf457cd9bc431db4e43c124e14",
+                "fetch_kib": 1461735.0, "fetch_scale": 1.99992, "write_kib": 1182295.6, "write_scale": 1.0},
     "k_r3_mm": {"source": "paper_2602_06986_amd/csrc/dsc_r3.hip",
-                "sha256": "81ba33d12238a00f2f4a824bf5b21a4e4d9f95730669143c6fba0b5f4321430d",
-                "fetch_kib": 6180863.9, "fetch_scale": 1.99992, "write_kib": 1299419.7, "write_scale": 1.0},
+                "sha256": "82721cb4e10461cbb8c43d98119a9ec1dab68aaf457cd9bc431db4e43c124e14",
+                "fetch_kib": 6167460.7, "fetch_scale": 1.99992, "write_kib": 1299340.8, "write_scale": 1.0},
 }
 
 

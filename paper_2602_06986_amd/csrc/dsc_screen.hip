@@ -1289,12 +1289,40 @@ __device__ __forceinline__ void d_compact(const double* __restrict__ sc, int64_t
     radix_finish1(hist, K, gsel, gst, sel, st);        // one level: a lower bound suffices here
     const double th = select_threshold(sel, st);
     const double lo = st[1] ? 0.0 : th - 2.0 * margin;
-    // one atomic per wave: lanes take consecutive slots in lane order; four
-    // strided rows of 64 scores are loaded before any is tested, so the
-    // loads overlap (the pool's order does not matter: it is sorted later)
+    // Each wave gathers its hits in its own LDS queue (lane order within a
+    // row) and appends the queue to the pool with one atomic when it is full
+    // and once at the end, so a wave does not wait on a global atomic per
+    // row that holds a hit; four strided rows of 64 scores are loaded before
+    // any is tested, so the loads overlap (the pool's order does not matter:
+    // it is sorted later).  The slots are decoded into IDs at the flush,
+    // where the lanes' loads overlap too.
+    constexpr unsigned QN = 256;
+    __shared__ int64_t qs[4][QN];
+    __shared__ double qx[4][QN];
     const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
     const uint64_t below = (1ull << lane) - 1ull;
     const int64_t stride = (int64_t)gridDim.x * 256;
+    unsigned qn = 0;                                      // queued (wave-uniform)
+    auto flush = [&]() {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(cnt, (unsigned long long)qn);
+        base = __shfl(base, 0, 64);
+        for (unsigned e = lane; e < qn; e += 64) {
+            const unsigned long long slot = base + e;
+            if ((int64_t)slot < cap) {
+                pool[slot] = slot_id(sm, sd, qs[wv][e]);
+                pscr[slot] = qx[wv][e];                   // the screening score, for the rescore
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        qn = 0;
+    };
     for (int64_t i0 = (int64_t)blockIdx.x * 256 + (threadIdx.x & ~63); i0 < N; i0 += 4 * stride) {
         double xs[4];
 #pragma unroll
@@ -1309,18 +1337,17 @@ __device__ __forceinline__ void d_compact(const double* __restrict__ sc, int64_t
             const bool take = (x > 0.0 && x >= lo) || (x < 0.0 && -x >= lo);
             const uint64_t m = __builtin_amdgcn_ballot_w64(take);
             if (!m) continue;                             // (wave-uniform)
-            unsigned long long base = 0;
-            if (lane == 0) base = atomicAdd(cnt, (unsigned long long)__popcll(m));
-            base = __shfl(base, 0, 64);
+            const unsigned h = (unsigned)__popcll(m);
+            if (qn + h > QN) flush();
             if (take) {
-                const unsigned long long slot = base + __popcll(m & below);
-                if ((int64_t)slot < cap) {
-                    pool[slot] = slot_id(sm, sd, i);
-                    pscr[slot] = x;                       // the screening score, for the rescore
-                }
+                const unsigned e = qn + (unsigned)__popcll(m & below);
+                qs[wv][e] = i;
+                qx[wv][e] = x;
             }
+            qn += h;
         }
     }
+    if (qn) flush();
 }
 
 // Exact FP64 rescore of the pool (one wave per entry); also flags entries
