@@ -40,7 +40,6 @@ struct R3Plan {
     int n_as_ctiles = 0;
     int2* as_work = nullptr;
     int64_t n_as_work = 0;
-    int32_t* as_gidx = nullptr;       // per add/sub record: its index in grec (score slots)
     uint32_t ops = 0;                 // rung-3 binary operators (bit o - OP_ADD)
     int pe = 0;                       // partner pool size (compact 0..pe-1)
     std::vector<void*> allocs;

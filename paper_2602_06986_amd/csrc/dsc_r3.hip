@@ -250,7 +250,6 @@ struct R3mArgs {
     const double* ysum;
     SpaceDev sd;
     SlotMap sm;
-    const int32_t* gidx;      // add / sub: grec index of each record (score slots)
     int64_t N;
     double* scores;
     unsigned long long* nscored;
@@ -267,8 +266,8 @@ __global__ __launch_bounds__(256) void k_r3_mm(R3mArgs g) {
     const int r16 = lane & 15, kq = lane >> 4;
     int ct;
     int64_t tile0;
+    const int64_t w = (int64_t)blockIdx.x * 4 + r3_wave();   // add / sub: the work item
     if (AS) {                                          // explicit (row tile, column tile) list
-        const int64_t w = (int64_t)blockIdx.x * 4 + r3_wave();
         if (w >= g.n_work) return;
         const int2 wk = g.work[w];
         tile0 = wk.x;
@@ -410,7 +409,6 @@ __global__ __launch_bounds__(256) void k_r3_mm(R3mArgs g) {
             gs[TP + 1] = __shfl(acc[0][TP + 1][r], src, 64);
             const bool ok = __shfl((int)rok[0], i, 64) != 0 && colok;
             if (!ok) continue;
-            const int64_t gr = g.gidx[tile0 * 16 + i];  // the row's rung-2 record
             const double* pc = g.pconst + (int64_t)p * TK;
             const double Sxg = acc[0][TP][r];
             const double A = pc[TP + 1] + gs[TP + 1];
@@ -418,7 +416,7 @@ __global__ __launch_bounds__(256) void k_r3_mm(R3mArgs g) {
             for (int o = 0; o < 2; o++) {
                 if (!((g.ops >> o) & 1u)) continue;
                 const double sg = o == 0 ? 1.0 : -1.0;
-                const int64_t id = slot3(g.sm, OP_ADD + o, gr, p);
+                const int64_t id = slot3as(g.sm, OP_ADD + o, w, i, r16);   // score slot
                 const double S1 = pc[TP] + sg * gs[TP];
                 const double S2 = pc[TP + 1] + 2.0 * sg * Sxg + gs[TP + 1];
                 const double varn = S2 - S1 * (S1 / nn);
@@ -1051,7 +1049,7 @@ std::shared_ptr<R3Plan> build_r3_plan(const Space& sp, uint32_t r3_ops) {
             if (pg.count(kk)) byk[kk][(int)((unsigned)rec[r].y >> 28)].push_back(r);
         }
         std::vector<int2> arec, work;
-        std::vector<int32_t> acols, agidx;
+        std::vector<int32_t> acols;
         for (auto& e : byk) {
             const std::vector<int32_t>& pl = pg[e.first];
             const int ct0 = (int)(acols.size() / 16);
@@ -1062,14 +1060,8 @@ std::shared_ptr<R3Plan> build_r3_plan(const Space& sp, uint32_t r3_ops) {
             const int ct1 = (int)(acols.size() / 16);
             for (auto& ro : e.second) {
                 const int64_t rt0 = (int64_t)arec.size() / 16;
-                for (int64_t r : ro.second) {
-                    arec.push_back(rec[r]);
-                    agidx.push_back((int32_t)r);
-                }
-                while (arec.size() % 16) {
-                    arec.push_back(make_int2(-2, ro.first << 28));
-                    agidx.push_back(0);
-                }
+                for (int64_t r : ro.second) arec.push_back(rec[r]);
+                while (arec.size() % 16) arec.push_back(make_int2(-2, ro.first << 28));
                 const int64_t rt1 = (int64_t)arec.size() / 16;
                 for (int64_t rt = rt0; rt < rt1; rt++)
                     for (int c = ct0; c < ct1; c++) work.push_back(make_int2((int)rt, c));
@@ -1083,7 +1075,6 @@ std::shared_ptr<R3Plan> build_r3_plan(const Space& sp, uint32_t r3_ops) {
             P->as_grec = r3_up(*P, arec);
             P->as_coldesc = r3_up(*P, acols);
             P->as_work = r3_up(*P, work);
-            P->as_gidx = r3_up(*P, agidx);
         }
     }
     return P;
@@ -1162,7 +1153,7 @@ void launch_r3(discover_ctx* ctx, const R3Launch& a, hipStream_t st) {
         check_launch("k_r3_ybmat");
         R3mArgs m{};
         m.grec = P.as_grec; m.n_grec = P.n_as_grec; m.work = P.as_work; m.n_work = P.n_as_work;
-        m.pconst = pc; m.coldesc = P.as_coldesc; m.n_gct = 0; m.ybmat = yb; m.gidx = P.as_gidx;
+        m.pconst = pc; m.coldesc = P.as_coldesc; m.n_gct = 0; m.ybmat = yb;
         m.NQ = NQ; m.n = a.n; m.T = a.T; m.mode = a.mode; m.ldn = a.ldn; m.bmat = bm;
         m.Vf = a.Vf; m.Rf = a.Rf; m.pstat = a.pstat; m.pe = P.pe; m.ops = P.ops;
         m.valid = a.valid; m.mat_raw = a.mat_raw; m.r2v = a.r2v; m.ysum = a.ysum; m.sd = a.sd;

@@ -2928,12 +2928,17 @@ static std::shared_ptr<Plan> get_plan(discover_ctx* ctx, const discover_problem&
         P->sm.pe = std::max(r3.pe, 1);
         P->sm.grec = r3.grec;
         P->sm.mat_raw = P->mat_raw;
+        P->sm.as_grec = r3.as_grec;
+        P->sm.as_work = r3.as_work;
+        P->sm.as_cols = r3.as_coldesc;
         int64_t s = sd.off[3];
-        for (int q = 0; q < 5; q++)
-            if (sd.block[3][OP_ADD + q] >= 0 && r3.n_grec && r3.pe) {
+        for (int q = 0; q < 5; q++) {
+            const int64_t sz = q < 2 ? r3.n_as_work * 256 : r3.n_grec * r3.pe;
+            if (sd.block[3][OP_ADD + q] >= 0 && sz > 0) {
                 P->sm.sblk[q] = s;
-                s += r3.n_grec * r3.pe;
+                s += sz;
             }
+        }
         P->sm.n = s;
     }
     ctx->plans[key] = P;

@@ -75,35 +75,54 @@ __host__ __device__ inline void decode_id(const SpaceDev& s, int64_t id, int& ru
 }
 
 // Score slots of one problem's candidates.  IDs below s3 are their own
-// slots.  With an operator-limited rung 3 only the unit-legal rung-2
-// features (the records of the rung-3 plan, padding included) get rung-3
-// slots: binary operator OP_ADD + q, record r and partner c (compact) has
-// slot sblk[q] + r pe + c.  The rung-3 slot space is then the size of the
-// unit-legal part of the rung instead of the raw one, and so are the fill,
-// histogram and compaction passes over it.
+// slots.  With an operator-limited rung 3 only the unit-legal pairs get
+// rung-3 slots: mul / div / rdiv (OP_ADD + q, q >= 2) of record r (a
+// unit-legal rung-2 feature of the rung-3 plan, padding included) and
+// partner c (compact) has slot sblk[q] + r pe + c; add / sub (q < 2), legal
+// only between equal unit vectors, have slot sblk[q] + (16 w + i) 16 + j for
+// row i and column j of add/sub work item w.  The rung-3 slot space is then
+// about the size of the unit-valid part of the rung instead of the raw one,
+// and so are the fill, histogram and compaction passes over it.
 struct SlotMap {
     int64_t s3 = 0;           // first rung-3 slot (= first rung-3 ID)
     int64_t n = 0;            // slots
     int64_t sblk[5] = {-1, -1, -1, -1, -1};   // ascending where enabled, -1 disabled
     int32_t pe = 1;           // partners
     const int2* grec = nullptr;       // records: k (-1 unary, -2 padding), l | op2 << 28
+    const int2* as_grec = nullptr;    // add / sub records, work items (row tile,
+    const int2* as_work = nullptr;    // column tile) and column tiles (partner
+    const int32_t* as_cols = nullptr; // | kind << 16)
     const int64_t* mat_raw = nullptr; // compact -> raw operand index
 };
 
-// Rung-3 slot of (operator o, record r, partner c).
+// Rung-3 slot of (mul / div / rdiv operator o, record r, partner c).
 __host__ __device__ inline int64_t slot3(const SlotMap& m, int o, int64_t r, int c) {
     return m.sblk[o - OP_ADD] + r * m.pe + c;
 }
+// Rung-3 slot of (add / sub operator o, work item w, row i, column j).
+__host__ __device__ inline int64_t slot3as(const SlotMap& m, int o, int64_t w, int i, int j) {
+    return m.sblk[o - OP_ADD] + ((w * 16 + i) << 4) + j;
+}
 
-// ID of a slot (-1 for a padding record's slot, which is never written).
+// ID of a slot (-1 for a padding slot, which is never written).
 __device__ inline int64_t slot_id(const SlotMap& m, const SpaceDev& s, int64_t slot) {
     if (slot < m.s3 || !m.grec) return slot;
     int q = 4;
     while (q > 0 && (m.sblk[q] < 0 || slot < m.sblk[q])) q--;
-    const int64_t w = slot - m.sblk[q];
-    const int64_t r = w / m.pe;
-    const int c = (int)(w - r * m.pe);
-    const int2 rc = m.grec[r];
+    const int64_t v = slot - m.sblk[q];
+    int2 rc;
+    int c;
+    if (q < 2) {
+        const int2 wk = m.as_work[v >> 8];
+        rc = m.as_grec[(int64_t)wk.x * 16 + ((v >> 4) & 15)];
+        const int32_t cd = m.as_cols[wk.y * 16 + (v & 15)];
+        if (cd < 0 || (cd >> 16) != 0) return -1;
+        c = cd & 0xFFFF;
+    } else {
+        const int64_t r = v / m.pe;
+        c = (int)(v - r * m.pe);
+        rc = m.grec[r];
+    }
     const int k = rc.x, l = rc.y & 0x0FFFFFFF, op2 = (int)((unsigned)rc.y >> 28);
     if (k == -2) return -1;
     const int64_t j2 = k < 0 ? unary_id(s, 2, op2, m.mat_raw[l]) : pair_id(s, 2, op2, m.mat_raw[k], m.mat_raw[l]);
