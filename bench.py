@@ -53,11 +53,11 @@ SWEEP3_COUNTERS = {
 R3_COUNTERS = {
     # the precision form: totals of the k_r3_lp kernels of one dimension
     "k_r3_lp": {"source": "paper_2602_06986_amd/csrc/dsc_r3.hip",
-                "sha256": "82721cb4e10461cbb8c43d98119a9ec1dab68aaf457cd9bc431db4e43c124e14",
-                "fetch_kib": 1461735.0, "fetch_scale": 1.99992, "write_kib": 1182295.6, "write_scale": 1.0},
+                "sha256": "a2bf91b51baca1994c6469e422a2778039c7954ce4f4a2faa4626fa30195b7e6",
+                "fetch_kib": 1471844.9, "fetch_scale": 1.99992, "write_kib": 1173390.8, "write_scale": 1.0},
     "k_r3_mm": {"source": "paper_2602_06986_amd/csrc/dsc_r3.hip",
-                "sha256": "82721cb4e10461cbb8c43d98119a9ec1dab68aaf457cd9bc431db4e43c124e14",
-                "fetch_kib": 6167460.7, "fetch_scale": 1.99992, "write_kib": 1299340.8, "write_scale": 1.0},
+                "sha256": "a2bf91b51baca1994c6469e422a2778039c7954ce4f4a2faa4626fa30195b7e6",
+                "fetch_kib": 6172460.2, "fetch_scale": 1.99992, "write_kib": 1299340.4, "write_scale": 1.0},
 }
 
 
