@@ -1477,6 +1477,66 @@ __device__ __forceinline__ bool rules_pass(const RuleTab& R, const Cand& c) {
     return true;
 }
 
+// The pool is rescored in two stages.  Stage 0 takes the entries whose
+// screening score reaches the selection's lower bound th (at least K of
+// them) and histograms their exact scores; the K-th largest of those, a
+// lower bound theta1 of the K-th largest exact score, then spares stage 1
+// every remaining entry whose score cannot reach it (|screening| + margin <
+// theta1): those are marked not selectable, and the groups count the pool
+// complete only down to max(th - margin, theta1).  d_split lists each
+// stage's pool positions (pex = 2 marks a position left to stage 1).
+__device__ __forceinline__ void d_split(int stage, const unsigned long long* __restrict__ Pp, int64_t cap,
+                                        const uint32_t* __restrict__ sel, const int64_t* __restrict__ st,
+                                        double margin, int64_t K, const uint32_t* __restrict__ hist1,
+                                        uint32_t* __restrict__ th1d, double* __restrict__ perr,
+                                        uint8_t* __restrict__ pex, double* __restrict__ ps,
+                                        int32_t* __restrict__ rank, int32_t* __restrict__ order,
+                                        const PoolVals pvs, int32_t* __restrict__ lst,
+                                        unsigned long long* __restrict__ lcnt) {
+    const int64_t P = min((int64_t)*Pp, cap);
+    const bool all = st[1] != 0;
+    const double th = select_threshold(sel, st);
+    double th1 = 0.0;
+    if (stage == 1) {
+        const RadixDigit d = radix_digit(hist1, K, false);
+        th1 = d.all ? 0.0 : (double)d.digit * 2.44140625e-4;          // digit * 2^-12
+        if (blockIdx.x == 0 && threadIdx.x == 0) *th1d = d.all ? 0u : d.digit + 1u;
+    }
+    const int lane = threadIdx.x & 63;
+    const uint64_t below = (1ull << lane) - 1ull;
+    const int64_t l0 = stage == 0 ? 0 : (int64_t)lcnt[0];
+    for (int64_t i0 = (int64_t)blockIdx.x * 256 + (threadIdx.x & ~63); i0 < P; i0 += (int64_t)gridDim.x * 256) {
+        const int64_t w = i0 + lane;
+        bool take = false;
+        if (w < P) {
+            const double x = fabs(perr[w]);               // the screening score (stage 0)
+            if (stage == 0) {
+                take = all || x >= th;
+                if (!take) pex[w] = 2;
+            } else if (pex[w] == 2) {
+                take = x + margin >= th1;
+                if (!take) {                              // cannot reach the K-th exact score
+                    ps[w] = -1.0;
+                    pex[w] = 0;
+                    rank[w] = 0;
+                    order[w] = (int32_t)w;
+                    perr[w] = 0.0;
+                    if (w < pvs.cap) {
+                        pvs.mean[w] = __longlong_as_double(0x7FF8000000000000LL);
+                        pvs.sxx[w] = __longlong_as_double(0x7FF8000000000000LL);
+                    }
+                }
+            }
+        }
+        const uint64_t m = __builtin_amdgcn_ballot_w64(take);
+        if (!m) continue;                                 // (wave-uniform)
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(&lcnt[stage], (unsigned long long)__popcll(m));
+        base = __shfl(base, 0, 64);
+        if (take) lst[l0 + (int64_t)(base + __popcll(m & below))] = (int32_t)w;
+    }
+}
+
 // Exact scores of the pool, four entries per block (one per wave) in step:
 // the first pass (values, mean, finiteness) per wave; in the second the
 // block stages the centred targets of each 64-sample chunk in LDS once
@@ -1497,13 +1557,19 @@ __device__ __forceinline__ void d_rescore(const int64_t* __restrict__ pool,
                                                  double* __restrict__ perr,
                                                  int32_t* __restrict__ rank,
                                                  int32_t* __restrict__ order,
-                                                 const PoolVals pvs, const RuleTab* __restrict__ rules) {
-    const int64_t P = min((int64_t)*Pp, cap);
+                                                 const PoolVals pvs, const RuleTab* __restrict__ rules,
+                                                 const int32_t* __restrict__ lst,
+                                                 const unsigned long long* __restrict__ lcnt, int stage,
+                                                 uint32_t* __restrict__ hist1) {
+    // the entries of this stage: positions lst[l0 .. l0 + P) of the pool
+    const int64_t l0 = stage == 0 ? 0 : (int64_t)lcnt[0];
+    const int64_t P = min((int64_t)lcnt[stage], cap - l0);
     const int lane = threadIdx.x & 63;
     __shared__ double ys[2][TMAX][64];
     for (int64_t g = blockIdx.x; g * 4 < P; g += gridDim.x) {      // uniform over the block
-    const int64_t w = g * 4 + wave_id();
-    const bool has = w < P;
+    const int64_t wl = g * 4 + wave_id();
+    const bool has = wl < P;
+    const int64_t w = has ? lst[l0 + wl] : 0;
     const int64_t id = has ? pool[w] : 0;
     Cand c;
     bool ok = has && cand_of_id(ev, id, c);
@@ -1586,7 +1652,7 @@ __device__ __forceinline__ void d_rescore(const int64_t* __restrict__ pool,
     int ex = 0;
     for (int e = lane; e < n_excl; e += 64) ex |= excl[e] == id;
     ex = __any(ex);
-    if (lane == 0) {
+    if (lane == 0 && has) {
         double s = -1.0;
         if (ok) {
             if (mode == DISCOVER_SCORE_MAX) {
@@ -1603,6 +1669,7 @@ __device__ __forceinline__ void d_rescore(const int64_t* __restrict__ pool,
         order[w] = (int32_t)w;                            // (a valid index even before the scatter)
         const double x = perr[w];                         // screening-pass score (from the compaction)
         perr[w] = s > 0.0 && x > 0.0 ? fabs(x - s) : 0.0; // its maximum is taken by k_groups
+        if (stage == 0 && s > 0.0) atomicAdd(&hist1[fx_key(s) >> 40], 1u);
     }
     }
 }
@@ -2209,15 +2276,18 @@ __device__ __forceinline__ void d_groups(
     const int64_t* __restrict__ pool, const double* __restrict__ ps, const uint8_t* __restrict__ pex,
     const int32_t* __restrict__ order, const unsigned long long* __restrict__ Pp, int64_t cap,
     double tail, int k, const uint32_t* __restrict__ sel,
-    const int64_t* __restrict__ st, double margin, int32_t* __restrict__ parent,
-    int32_t* __restrict__ blk, unsigned long long* __restrict__ repid, int32_t* __restrict__ reppos,
+    const int64_t* __restrict__ st, double margin, const uint32_t* __restrict__ th1d,
+    int32_t* __restrict__ parent, int32_t* __restrict__ blk, unsigned long long* __restrict__ repid, int32_t* __restrict__ reppos,
     int32_t* __restrict__ headpos, int64_t* __restrict__ out_ids, double* __restrict__ out_sc,
     int64_t* __restrict__ res) {
     __shared__ int64_t part[GRP_THREADS];
     const int64_t P = min((int64_t)*Pp, cap);
     const int t = threadIdx.x;
     const bool all = st[1] != 0;
-    const double th_scan = all ? -1.0 : select_threshold(sel, st) - margin;
+    // the pool is complete down to th - margin, and down to theta1 where the
+    // two-stage rescoring spared entries below it
+    const double th_scan = all ? -1.0 : fmax(select_threshold(sel, st) - margin,
+                                             *th1d ? (double)(*th1d - 1u) * 2.44140625e-4 : 0.0);
     const int32_t* vpar = parent;                          // heads, set by k_clusters / k_dedup
     for (int64_t q = t; q < P; q += GRP_THREADS) {
         blk[q] = 0;
@@ -2318,7 +2388,7 @@ __device__ __forceinline__ void d_groups_lds(
     const int64_t* __restrict__ pool, const double* __restrict__ ps, const uint8_t* __restrict__ pex,
     const int32_t* __restrict__ order, const int32_t* __restrict__ parent, int64_t P, double tail, int k,
     const uint32_t* __restrict__ sel, const int64_t* __restrict__ st, double margin,
-    int32_t* __restrict__ headpos, int64_t* __restrict__ out_ids, double* __restrict__ out_sc,
+    const uint32_t* __restrict__ th1d, int32_t* __restrict__ headpos, int64_t* __restrict__ out_ids, double* __restrict__ out_sc,
     int64_t* __restrict__ res, const PoolVals pvs, int64_t* __restrict__ vrow) {
     __shared__ int64_t part[GRP_THREADS];
     __shared__ __align__(16) int32_t par[GRP_LDS];
@@ -2326,7 +2396,10 @@ __device__ __forceinline__ void d_groups_lds(
     __shared__ uint32_t blkb[GRP_LDS / 32];
     const int t = threadIdx.x;
     const bool all = st[1] != 0;
-    const double th_scan = all ? -1.0 : select_threshold(sel, st) - margin;
+    // the pool is complete down to th - margin, and down to theta1 where the
+    // two-stage rescoring spared entries below it
+    const double th_scan = all ? -1.0 : fmax(select_threshold(sel, st) - margin,
+                                             *th1d ? (double)(*th1d - 1u) * 2.44140625e-4 : 0.0);
     for (int q = t; q < P; q += GRP_THREADS) {             // heads, set by k_clusters / k_dedup
         par[q] = parent[q];
         rkey[q] = ~0ull;
@@ -2536,6 +2609,7 @@ struct SelArgs {
     unsigned long long* rkr;  // rank buckets' key range
     double* ss;               // scores in sorted order
     double* perr;             // per pool entry: its screening score, then |screening - exact|
+    uint32_t* th1d;           // two-stage rescoring: digit of theta1 + 1 (0: none)
     int64_t* off;
     uint8_t* flag;
     unsigned long long* ncl;  // near-tie clusters listed in wc (starts)
@@ -2561,12 +2635,20 @@ __global__ __launch_bounds__(256) void k_compact(ctab<SelArgs> A) {
 // TM: the most targets of any list of the launch (1, 8 or 16 registers of
 // sums per lane).
 template <int TM>
-__global__ __launch_bounds__(256) void k_rescore(ctab<SelArgs> A) {
+__global__ __launch_bounds__(256) void k_rescore(ctab<SelArgs> A, int stage) {
     const SelArgs& a = tab(A, blockIdx.y);
     DSC_GLOBAL(a.sc); DSC_GLOBAL(a.sel); DSC_GLOBAL(a.st); DSC_GLOBAL(a.pool); DSC_GLOBAL(a.cnt); DSC_GLOBAL(a.ev.raw2c); DSC_GLOBAL(a.ev.valid); DSC_GLOBAL(a.o.Vf); DSC_GLOBAL(a.o.Rf); DSC_GLOBAL(a.Yc); DSC_GLOBAL(a.syy); DSC_GLOBAL(a.ps); DSC_GLOBAL(a.pex); DSC_GLOBAL(a.maxerr); DSC_GLOBAL(a.order); DSC_GLOBAL(a.lo); DSC_GLOBAL(a.wc); DSC_GLOBAL(a.off); DSC_GLOBAL(a.flag); DSC_GLOBAL(a.parent); DSC_GLOBAL(a.blk); DSC_GLOBAL(a.repid); DSC_GLOBAL(a.reppos); DSC_GLOBAL(a.headpos); DSC_GLOBAL(a.out_ids); DSC_GLOBAL(a.out_sc); DSC_GLOBAL(a.res);
     d_rescore<TM>(a.pool, a.cnt, a.cap, a.ev, a.o, a.n, a.T, a.mode, a.t, a.Yc, a.syy,
                                     a.excl, a.n_excl, a.ps, a.pex, a.perr, a.rank, a.order, a.pvs,
-                                    a.rules);
+                                    a.rules, a.lo, a.rkr + 4, stage, (uint32_t*)a.hist + 4096);
+}
+
+// grid (blocks, lists): the pool positions of one rescoring stage (the
+// list in lo, its counts in rkr[4], rkr[5]; both free until the sort)
+__global__ __launch_bounds__(256) void k_split(ctab<SelArgs> A, int stage) {
+    const SelArgs& a = tab(A, blockIdx.y);
+    d_split(stage, a.cnt, a.cap, a.sel, a.st, a.margin, a.K, a.hist + 4096, a.th1d, a.perr, a.pex, a.ps,
+            a.rank, a.order, a.pvs, a.lo, a.rkr + 4);
 }
 
 // grid (i tiles, j chunks, lists)
@@ -2648,12 +2730,12 @@ __global__ __launch_bounds__(GRP_THREADS) void k_groups(ctab<SelArgs> A) {
     const double tail = Pd < P ? a.ps[a.order[Pd]] : -1.0;
     if (Pd <= GRP_LDS) {
         d_groups_lds(a.pool, a.ps, a.pex, a.order, a.parent, Pd, tail, a.k, a.sel, a.st, a.margin,
-                     a.headpos, a.out_ids, a.out_sc, a.res, a.pvs, a.vrow);
+                     a.th1d, a.headpos, a.out_ids, a.out_sc, a.res, a.pvs, a.vrow);
         if (threadIdx.x == 0) a.res[4] = (int64_t)*a.cnt;     // pool size (capacity check)
         return;
     }
     for (int64_t i = threadIdx.x; i < a.k; i += GRP_THREADS) a.vrow[i] = 0;   // rows are evaluated
-    d_groups(a.pool, a.ps, a.pex, a.order, a.cnt, a.cap, tail, a.k, a.sel, a.st, a.margin, a.parent, a.blk,
+    d_groups(a.pool, a.ps, a.pex, a.order, a.cnt, a.cap, tail, a.k, a.sel, a.st, a.margin, a.th1d, a.parent, a.blk,
              a.repid, a.reppos, a.headpos, a.out_ids, a.out_sc, a.res);
 }
 
@@ -3595,6 +3677,7 @@ static void select_round(discover_ctx* ctx, const discover_problem* probs,
         a.pd = (unsigned long long*)(misc + 56);
         int64_t* stv = (int64_t*)(misc + 16);
         uint32_t* sel = (uint32_t*)(misc + 32);
+        a.th1d = (uint32_t*)(misc + 44);
         a.sel = sel; a.st = stv; a.hist = hist;
         a.sc = P.scores + (int64_t)L.t * P.N; a.N = P.N;
         a.margin = margin[L.b]; a.cap = L.cap; a.fcap = L.fcap; a.K = L.K;
@@ -3631,9 +3714,13 @@ static void select_round(discover_ctx* ctx, const discover_problem* probs,
         int Tm = 1;
         for (const SelArgs& x : sa) Tm = std::max(Tm, x.T);
         const dim3 rg((unsigned)std::min<int64_t>(std::max(64, 2048 / nl), cdiv(capmax, 4)), nl);
-        if (Tm <= 1) k_rescore<1><<<rg, 256, 0, st>>>(dsa);
-        else if (Tm <= 8) k_rescore<8><<<rg, 256, 0, st>>>(dsa);
-        else k_rescore<DISCOVER_MAX_TARGETS><<<rg, 256, 0, st>>>(dsa);
+        const dim3 sg((unsigned)std::min<int64_t>(1024, cdiv(capmax, 256)), nl);
+        for (int stage = 0; stage < 2; stage++) {
+            k_split<<<sg, 256, 0, st>>>(dsa, stage);
+            if (Tm <= 1) k_rescore<1><<<rg, 256, 0, st>>>(dsa, stage);
+            else if (Tm <= 8) k_rescore<8><<<rg, 256, 0, st>>>(dsa, stage);
+            else k_rescore<DISCOVER_MAX_TARGETS><<<rg, 256, 0, st>>>(dsa, stage);
+        }
         check_launch("k_rescore");
     }
     {
