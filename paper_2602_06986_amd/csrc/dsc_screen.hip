@@ -12,7 +12,8 @@
 //     valid     [Mc]        operand usable (finite, non-constant, valid operands)
 //   targets: Yc [T][ldn] centered, Yn [Tp][ldn] centered and unit-norm
 //            (rows >= T are zero padding), syy [T], ysum [Tp] = sum Yn
-//   scores    [T'][N]       one FP64 slot per candidate ID:
+//   scores    [T'][N]       one FP64 slot per candidate (the ID below rung 3;
+//                           unit-legal rung-3 pairs through the slot map):
 //                             +s     score with |error| <= margin
 //                             -u     error may be larger; u bounds s above
 //                             NaN    invalid / unit-illegal / not computed
