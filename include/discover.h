@@ -168,7 +168,10 @@ typedef struct {
     int64_t n_raw;            /* |P_R|: every enumerated candidate */
     int64_t n_unit_valid;     /* candidates passing the unit rules */
     int64_t n_scored;         /* candidates with a finite, non-constant value vector */
-    int64_t pool_size;        /* candidates rescored exactly (summed over lists) */
+    int64_t pool_size;        /* candidates in the selection pools (summed over lists);
+                                 exactly rescored are those of them whose screening
+                                 score plus the margin reaches a lower bound of the
+                                 K-th exact score */
     int64_t pool_rounds;      /* pool enlargements needed (0 normally) */
     int64_t n_merged;         /* duplicates merged into an earlier group */
     int64_t n_selected;       /* selected features (summed over lists) */
